@@ -1,0 +1,209 @@
+"""CHERT CPU oracle -- test infrastructure only.
+
+A plain FP64 C implementation (``chert_oracle.c``) of what the CHERT hot path
+computes, wrapped with ctypes.  Only the tests, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py`` may import this package.  It shares
+no code with the HIP library (``paper_2609_26108_amd``) and neither imports
+the other.
+
+Every function cites the passage of the paper it follows in the C source.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "chert_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+QP, QSV, QSH = 0, 1, 2
+MEV, OEV = 0, 1
+ST_OK, ST_NO_BRACKET, ST_ILL, ST_FLUID, ST_NONPHYS = 0, 1, 2, 4, 8
+FIELDS = ("V", "A", "Q", "rx", "rz", "thR", "thI", "res")
+NF = len(FIELDS)
+N_SWEEP = 1440
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with plain IEEE settings (no fast-math, no FMA)."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fno-fast-math", "-ffp-contract=off",
+               "-fPIC", "-shared", "-o", tmp, SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        d, i, l, u = ctypes.c_double, ctypes.c_int, ctypes.c_long, ctypes.c_uint
+        P = ctypes.c_void_p
+        L.orc_thomsen.argtypes = [d, d, d, d, d, P]
+        L.orc_velocity.argtypes = [P, i, i, d, d, P]
+        L.orc_residual.argtypes = [P, i, i, d, d]
+        L.orc_residual.restype = d
+        L.orc_theta_imag.argtypes = [P, i, i, d, P]
+        L.orc_solve.argtypes = [P, i, i, i, d, P]
+        L.orc_sweep.argtypes = [P, i, i, i, P, P, P, P]
+        L.orc_build_cache_2d.argtypes = [P, l, i, u, i, i, P, P]
+        L.orc_star_2d.argtypes = [i, d, d, i, P, P, P, P]
+        L.orc_trace_2d.argtypes = [l, l, d, d, P, i, i, P, P, P, l,
+                                   P, P, P, P, P, P, P]
+        L.orc_trace_uncached_2d.argtypes = [l, l, d, d, P, P, i, i, i, i, i,
+                                            i, l, P, P]
+        L.orc_raypath.argtypes = [P, l, l, l, P, l, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+# ---------------------------------------------------------------- classes --
+
+def class_from_thomsen(vp0, vs0, rho, eps, delta, gamma, tilt, azimuth, qp, qs):
+    """13-double class: moduli (Thomsen 1986), Q per component (Qp on
+    a11/a13/a33, Qs on a44/a66), rho, tilt, azimuth."""
+    a5 = np.zeros(5)
+    rc = lib().orc_thomsen(vp0, vs0, eps, delta, gamma, _p(a5))
+    if rc != 0:
+        raise ValueError("negative a13 radicand")
+    return np.array([*a5, qp, qp, qp, qs, qs, rho, tilt, azimuth], dtype=np.float64)
+
+
+def class_from_moduli(a11, a13, a33, a44, a66, q11, q13, q33, q44, q66,
+                      rho=0.0, tilt=0.0, azimuth=0.0):
+    return np.array([a11, a13, a33, a44, a66, q11, q13, q33, q44, q66,
+                     rho, tilt, azimuth], dtype=np.float64)
+
+
+# ------------------------------------------------------------ local solve --
+
+def velocity(cls, mode, thR, thI, reading=MEV):
+    """dict with complex v (2,), c, g (2,), p (2,) at (thR, thI), local frame."""
+    out = np.zeros(14)
+    c = np.ascontiguousarray(cls, dtype=np.float64)
+    lib().orc_velocity(_p(c), mode, reading, thR, thI, _p(out))
+    return {
+        "v": np.array([out[0] + 1j * out[2], out[1] + 1j * out[3]]),
+        "c": out[4] + 1j * out[5],
+        "g": np.array([out[6] + 1j * out[7], out[8] + 1j * out[9]]),
+        "p": np.array([out[10] + 1j * out[11], out[12] + 1j * out[13]]),
+    }
+
+
+def residual(cls, mode, thR, thI, reading=MEV):
+    c = np.ascontiguousarray(cls, dtype=np.float64)
+    return lib().orc_residual(_p(c), mode, reading, thR, thI)
+
+
+def theta_imag(cls, mode, thR, reading=MEV):
+    c = np.ascontiguousarray(cls, dtype=np.float64)
+    out = np.zeros(1)
+    rc = lib().orc_theta_imag(_p(c), mode, reading, thR, _p(out))
+    return None if rc else float(out[0])
+
+
+def solve(cls, mode, psi_local, reading=MEV, n_sweep=N_SWEEP):
+    """One target local ray angle -> (dict of fields, status).  Direction in
+    the local frame."""
+    c = np.ascontiguousarray(cls, dtype=np.float64)
+    out = np.zeros(NF)
+    st = lib().orc_solve(_p(c), mode, reading, n_sweep, psi_local, _p(out))
+    return dict(zip(FIELDS, out)), st
+
+
+def sweep(cls, mode, reading=MEV, n_sweep=N_SWEEP):
+    c = np.ascontiguousarray(cls, dtype=np.float64)
+    thR, thI, psi = (np.zeros(n_sweep) for _ in range(3))
+    ok = np.zeros(n_sweep, dtype=np.int32)
+    lib().orc_sweep(_p(c), mode, reading, n_sweep, _p(thR), _p(thI), _p(psi), _p(ok))
+    return thR, thI, psi, ok
+
+
+def build_cache_2d(classes, n_dirs=360, mode_mask=0b111, reading=MEV,
+                   n_sweep=N_SWEEP):
+    """Returns (fields [NF][3][K][n_dirs], status [3][K][n_dirs])."""
+    classes = np.ascontiguousarray(np.atleast_2d(classes), dtype=np.float64)
+    K = classes.shape[0]
+    fields = np.full((NF, 3, K, n_dirs), np.nan)
+    status = np.zeros((3, K, n_dirs), dtype=np.int32)
+    rc = lib().orc_build_cache_2d(_p(classes), K, n_dirs, mode_mask, reading,
+                                  n_sweep, _p(fields), _p(status))
+    if rc:
+        raise ValueError(f"orc_build_cache_2d failed rc={rc}")
+    return fields, status
+
+
+# ------------------------------------------------------------------ graph --
+
+def star_2d(R, hx, hz, n_dirs=360):
+    n = lib().orc_star_2d(R, hx, hz, n_dirs, None, None, None, None)
+    ox = np.zeros(n, np.int32)
+    oz = np.zeros(n, np.int32)
+    L = np.zeros(n)
+    b = np.zeros(n, np.int32)
+    lib().orc_star_2d(R, hx, hz, n_dirs, _p(ox), _p(oz), _p(L), _p(b))
+    return ox, oz, L, b
+
+
+def trace_2d(nx, nz, hx, hz, class_id, R, V, A, status, src, n_dirs=360):
+    """Dijkstra traveltimes for one mode from a class cache slice
+    V/A/status [K][n_dirs].  Returns dict of tauR, tauI, predP, predA,
+    tstar, hopP, hopA."""
+    n = nx * nz
+    cid = np.ascontiguousarray(class_id, dtype=np.int32).reshape(-1)
+    assert cid.size == n
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    st = np.ascontiguousarray(status, dtype=np.int32)
+    out = {k: np.zeros(n) for k in ("tauR", "tauI", "tstar")}
+    out.update({k: np.zeros(n, np.int32) for k in ("predP", "predA", "hopP", "hopA")})
+    rc = lib().orc_trace_2d(nx, nz, hx, hz, _p(cid), R, n_dirs, _p(V), _p(A),
+                            _p(st), int(src), _p(out["tauR"]), _p(out["tauI"]),
+                            _p(out["predP"]), _p(out["predA"]), _p(out["tstar"]),
+                            _p(out["hopP"]), _p(out["hopA"]))
+    if rc:
+        raise ValueError(f"orc_trace_2d failed rc={rc}")
+    return out
+
+
+def trace_uncached_2d(nx, nz, hx, hz, class_id, classes, R, mode, field, src,
+                      n_dirs=360, reading=MEV, n_sweep=N_SWEEP):
+    n = nx * nz
+    cid = np.ascontiguousarray(class_id, dtype=np.int32).reshape(-1)
+    classes = np.ascontiguousarray(np.atleast_2d(classes), dtype=np.float64)
+    tau = np.zeros(n)
+    ns = ctypes.c_long(0)
+    rc = lib().orc_trace_uncached_2d(nx, nz, hx, hz, _p(cid), _p(classes), R,
+                                     n_dirs, mode, reading, n_sweep, field,
+                                     int(src), _p(tau), ctypes.byref(ns))
+    if rc:
+        raise ValueError("orc_trace_uncached_2d failed")
+    return tau, ns.value
+
+
+def raypath(pred, src, rcv, capacity=None):
+    """-> (rc, path array).  rc: 0 ok, 5 capacity, 6 unreachable, 7 cycle."""
+    pred = np.ascontiguousarray(pred, dtype=np.int32)
+    n = pred.size
+    cap = n if capacity is None else capacity
+    path = np.zeros(max(cap, 1), np.int64)
+    ln = ctypes.c_long(0)
+    rc = lib().orc_raypath(_p(pred), n, int(src), int(rcv), _p(path), cap,
+                           ctypes.byref(ln))
+    if rc == 5:
+        return rc, ln.value
+    return rc, (path[: ln.value].copy() if rc == 0 else None)

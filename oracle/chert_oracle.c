@@ -1,0 +1,962 @@
+/*
+ * CHERT CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously-correct FP64 implementation of what the CHERT hot
+ * path computes (Darwis, Bouchaala, Waheed, Riahi: "CHERT: Cached
+ * Hamiltonian-Enhanced Ray Tracing in Viscoelastic Anisotropic Media").
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load it.  It shares no source, header, table or helper with the HIP
+ * library, and the library never calls it.
+ *
+ * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fPIC -shared -lm
+ *
+ * Conventions (all SI; angles in radians):
+ *   - 2D frame: x to the right, z down; angles are measured from +z towards +x,
+ *     so the unit vector at angle a is (sin a, cos a) in (x, z).
+ *   - Symmetry axis of a tilted class: e_z' = (sin t0, cos t0) (eq 36), so a
+ *     global angle a is the local angle a - t0.
+ *   - Node index = ix + nx*iz.
+ *   - A class is 13 doubles: a11 a13 a33 a44 a66 (real density-normalised
+ *     moduli, m^2/s^2), q11 q13 q33 q44 q66 (quality factors, INFINITY =
+ *     elastic), rho (kept, unused by kinematics), tilt, azimuth.
+ *
+ * Readings of the paper that this file takes (the paper leaves them open):
+ *   - MEV (eq 14): the gradient of eq 13 with the eigenvector g and its
+ *     conjugate held fixed, symmetrised:  v_m = a_mjkl p_l Re(g_j g_k^*)/(g^H g).
+ *     OEV (eq 12): v_m = a_mjkl p_l g_j g_k/(g^T g).
+ *   - Per-component Q: a_pq = a_pq^R (1 - i/Q_pq) (eq 2).
+ *   - The imaginary slowness angle is the root of the homogeneity residual
+ *     nearest zero inside [-30 deg, 30 deg] (the search bracket of the local
+ *     benchmark section).  A mode whose moduli are all real is elastic:
+ *     theta_I = 0 exactly.
+ *   - The cache is indexed by ray direction: entry d holds the solution whose
+ *     ray direction is exactly d * 360/n_dirs degrees (global frame).  Where
+ *     several slowness angles give that ray direction (qSV triplication) the
+ *     one with the largest ray velocity (first arrival) is kept.
+ *   - Entries d >= n_dirs/2 are the centrosymmetric copies of d - n_dirs/2.
+ *   - Edge weights: endpoint-averaged velocity and attenuation (eqs 28-30) at
+ *     the bin of the edge direction; propagation and attenuation are two
+ *     independent shortest-path problems (eqs 24, 31).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+#define ORC_PI 3.14159265358979323846
+
+enum { ORC_QP = 0, ORC_QSV = 1, ORC_QSH = 2 };
+enum { ORC_MEV = 0, ORC_OEV = 1 };
+
+/* entry status bits */
+enum {
+  ORC_ST_OK = 0,
+  ORC_ST_NO_BRACKET = 1,  /* no slowness angle reaches the target ray direction */
+  ORC_ST_ILL = 2,         /* chosen root sits where d(psi)/d(theta_R) is tiny  */
+  ORC_ST_FLUID = 4,       /* shear mode in a medium without shear stiffness     */
+  ORC_ST_NONPHYS = 8      /* negative attenuation or non-finite ray quantities  */
+};
+
+/* output fields of one cache entry */
+enum { F_V = 0, F_A, F_Q, F_RX, F_RZ, F_THR, F_THI, F_RES, ORC_NF };
+
+#define ORC_THI_STEP (0.25 * ORC_PI / 180.0) /* outward scan step for theta_I */
+#define ORC_THI_MAX_STEPS 120                /* 120 * 0.25 deg = 30 deg      */
+#define ORC_THI_TOL 1e-15                    /* bisection width for theta_I  */
+#define ORC_THR_TOL 1e-14                    /* bisection width for theta_R  */
+#define ORC_ILL_SLOPE 1e-2                   /* |dpsi/dtheta_R| flag level   */
+#define ORC_TIE_REL 1e-12                    /* equal ray velocities         */
+
+/* ------------------------------------------------------------------------ */
+/* O-1  constitutive step (eq 2; Thomsen 1986 for the real part)           */
+/* ------------------------------------------------------------------------ */
+
+/* Thomsen (vp0, vs0, eps, delta, gamma) -> a11 a13 a33 a44 a66.
+ * Returns 0, or 1 when the a13 radicand is negative. */
+int orc_thomsen(double vp0, double vs0, double eps, double delta, double gamma,
+                double *a5) {
+  double a33 = vp0 * vp0;
+  double a44 = vs0 * vs0;
+  double rad = 2.0 * delta * a33 * (a33 - a44) + (a33 - a44) * (a33 - a44);
+  if (!(rad >= 0.0)) return 1;
+  a5[0] = a33 * (1.0 + 2.0 * eps);  /* a11 */
+  a5[1] = sqrt(rad) - a44;          /* a13 */
+  a5[2] = a33;                      /* a33 */
+  a5[3] = a44;                      /* a44 */
+  a5[4] = a44 * (1.0 + 2.0 * gamma);/* a66 */
+  return 0;
+}
+
+typedef struct {
+  cplx a11, a13, a33, a44, a66;
+  int elastic_ps; /* qP/qSV see only real moduli  */
+  int elastic_sh; /* qSH sees only real moduli    */
+  double tilt;
+} medium_t;
+
+static cplx complex_modulus(double aR, double q) {
+  /* eq 2: a = a^R - i a^I with a^I = a^R / Q;  Q = inf gives a real modulus */
+  double aI = isinf(q) ? 0.0 : aR / q;
+  return aR - I * aI;
+}
+
+static void load_medium(const double *c, medium_t *m) {
+  m->a11 = complex_modulus(c[0], c[5]);
+  m->a13 = complex_modulus(c[1], c[6]);
+  m->a33 = complex_modulus(c[2], c[7]);
+  m->a44 = complex_modulus(c[3], c[8]);
+  m->a66 = complex_modulus(c[4], c[9]);
+  m->elastic_ps = cimag(m->a11) == 0.0 && cimag(m->a13) == 0.0 &&
+                  cimag(m->a33) == 0.0 && cimag(m->a44) == 0.0;
+  m->elastic_sh = cimag(m->a44) == 0.0 && cimag(m->a66) == 0.0;
+  m->tilt = c[11];
+}
+
+static int mode_elastic(const medium_t *m, int mode) {
+  return mode == ORC_QSH ? m->elastic_sh : m->elastic_ps;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O-3  complex energy velocity at a trial slowness-angle pair              */
+/*      (eqs 4, 5, 7, 12, 14), in the local symmetry-axis frame             */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  cplx v1, v3;  /* complex energy velocity (x', z') */
+  cplx c;       /* complex phase velocity, Re c > 0 */
+  cplx g1, g3;  /* eigenvector (unnormalised)        */
+  cplx p1, p3;  /* complex slowness                   */
+} eval_t;
+
+static void energy_velocity(const medium_t *m, int mode, int reading,
+                            double thR, double thI, eval_t *e) {
+  cplx z = thR + I * thI;
+  cplx n1 = csin(z), n3 = ccos(z); /* eq 7 */
+  if (mode == ORC_QSH) {
+    /* SH polarisation is e_y: Gamma_22 = a66 n1^2 + a44 n3^2 */
+    cplx G = m->a66 * n1 * n1 + m->a44 * n3 * n3;
+    cplx c = csqrt(G);
+    cplx p1 = n1 / c, p3 = n3 / c; /* eq 5 */
+    e->c = c;
+    e->g1 = 0.0;
+    e->g3 = 0.0;
+    e->p1 = p1;
+    e->p3 = p3;
+    e->v1 = m->a66 * p1; /* a_1221 p_1 */
+    e->v3 = m->a44 * p3; /* a_3223 p_3 */
+    return;
+  }
+  /* Christoffel matrix of the sagittal plane for the unit direction n (eq 4) */
+  cplx G11 = m->a11 * n1 * n1 + m->a44 * n3 * n3;
+  cplx G33 = m->a44 * n1 * n1 + m->a33 * n3 * n3;
+  cplx G13 = (m->a13 + m->a44) * n1 * n3;
+  cplx mean = 0.5 * (G11 + G33);
+  cplx half = 0.5 * (G11 - G33);
+  cplx root = csqrt(half * half + G13 * G13);
+  cplx G = (mode == ORC_QP) ? mean + root : mean - root; /* qP: larger Re */
+  /* eigenvector: the better-conditioned of the two null-space forms */
+  cplx ua = G13, ub = G - G11;   /* from row 1 */
+  cplx wa = G - G33, wb = G13;   /* from row 2 */
+  double nu = creal(ua * conj(ua)) + creal(ub * conj(ub));
+  double nw = creal(wa * conj(wa)) + creal(wb * conj(wb));
+  cplx g1, g3;
+  if (nu >= nw) {
+    g1 = ua;
+    g3 = ub;
+  } else {
+    g1 = wa;
+    g3 = wb;
+  }
+  cplx c = csqrt(G);               /* G = c^2; principal root has Re c > 0 */
+  cplx p1 = n1 / c, p3 = n3 / c;   /* eq 5 */
+  cplx S11, S33, S13;
+  if (reading == ORC_OEV) {
+    cplx N = g1 * g1 + g3 * g3;    /* g^T g */
+    S11 = g1 * g1 / N;
+    S33 = g3 * g3 / N;
+    S13 = g1 * g3 / N;
+  } else {
+    double N = creal(g1 * conj(g1)) + creal(g3 * conj(g3)); /* g^H g */
+    S11 = creal(g1 * conj(g1)) / N;
+    S33 = creal(g3 * conj(g3)) / N;
+    S13 = creal(g1 * conj(g3)) / N;
+  }
+  /* v_m = a_mjkl p_l S_jk with the TI tensor (a_1111=a11, a_3333=a33,
+   * a_1133=a13, a_1313=a44) */
+  e->v1 = p1 * (m->a11 * S11 + m->a44 * S33) + p3 * (m->a13 + m->a44) * S13;
+  e->v3 = p3 * (m->a33 * S33 + m->a44 * S11) + p1 * (m->a13 + m->a44) * S13;
+  e->c = c;
+  e->g1 = g1;
+  e->g3 = g3;
+  e->p1 = p1;
+  e->p3 = p3;
+}
+
+/* Exported for tests: out = vR1 vR3 vI1 vI3 cR cI g1R g1I g3R g3I p1R p1I p3R p3I */
+int orc_velocity(const double *cls, int mode, int reading, double thR,
+                 double thI, double *out) {
+  medium_t m;
+  eval_t e;
+  load_medium(cls, &m);
+  energy_velocity(&m, mode, reading, thR, thI, &e);
+  out[0] = creal(e.v1);
+  out[1] = creal(e.v3);
+  out[2] = cimag(e.v1);
+  out[3] = cimag(e.v3);
+  out[4] = creal(e.c);
+  out[5] = cimag(e.c);
+  out[6] = creal(e.g1);
+  out[7] = cimag(e.g1);
+  out[8] = creal(e.g3);
+  out[9] = cimag(e.g3);
+  out[10] = creal(e.p1);
+  out[11] = cimag(e.p1);
+  out[12] = creal(e.p3);
+  out[13] = cimag(e.p3);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O-4  homogeneity residual (eq 9) and local ray angle                     */
+/* ------------------------------------------------------------------------ */
+
+/* sine of the angle between v^R and v^I: zero when they are collinear */
+static double homog_residual(const eval_t *e) {
+  double r1 = creal(e->v1), r3 = creal(e->v3);
+  double i1 = cimag(e->v1), i3 = cimag(e->v3);
+  double nr = sqrt(r1 * r1 + r3 * r3), ni = sqrt(i1 * i1 + i3 * i3);
+  return (r1 * i3 - r3 * i1) / (nr * ni);
+}
+
+static double ray_angle_local(const eval_t *e) {
+  return atan2(creal(e->v1), creal(e->v3));
+}
+
+double orc_residual(const double *cls, int mode, int reading, double thR,
+                    double thI) {
+  medium_t m;
+  eval_t e;
+  load_medium(cls, &m);
+  energy_velocity(&m, mode, reading, thR, thI, &e);
+  return homog_residual(&e);
+}
+
+/* ------------------------------------------------------------------------ */
+/* O-5  root searches                                                       */
+/* ------------------------------------------------------------------------ */
+
+static double h_at(const medium_t *m, int mode, int reading, double thR,
+                   double thI) {
+  eval_t e;
+  energy_velocity(m, mode, reading, thR, thI, &e);
+  return homog_residual(&e);
+}
+
+/* plain bisection of h(thR, .) on [lo, hi] with h(lo), h(hi) of opposite
+ * sign classes (negative / non-negative) */
+static double bisect_thi(const medium_t *m, int mode, int reading, double thR,
+                         double lo, double hi, double hlo) {
+  int neg_lo = hlo < 0.0;
+  for (int it = 0; it < 200 && hi - lo > ORC_THI_TOL; ++it) {
+    double mid = 0.5 * (lo + hi);
+    double hm = h_at(m, mode, reading, thR, mid);
+    if ((hm < 0.0) == neg_lo) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+/* does [a, b] with residuals ha, hb bracket a root?  (zero counts as
+ * non-negative, so a root exactly on a sample is bracketed exactly once) */
+static int brackets(double ha, double hb) {
+  if (isnan(ha) || isnan(hb)) return 0;
+  return (ha < 0.0) != (hb < 0.0);
+}
+
+/* theta_I(theta_R): the root of the homogeneity residual nearest zero in
+ * [-30 deg, 30 deg], found by scanning outwards from 0 in 0.25 deg steps.
+ * Returns 0 on success, 1 when there is no root in the bracket. */
+static int theta_imag(const medium_t *m, int mode, int reading, double thR,
+                      double *thI) {
+  if (mode_elastic(m, mode)) {
+    *thI = 0.0;
+    return 0;
+  }
+  double h0 = h_at(m, mode, reading, thR, 0.0);
+  if (h0 == 0.0) {
+    *thI = 0.0;
+    return 0;
+  }
+  double hp_lo = h0, hn_hi = h0; /* residuals at +k*step and -k*step */
+  for (int k = 0; k < ORC_THI_MAX_STEPS; ++k) {
+    double a = k * ORC_THI_STEP, b = (k + 1) * ORC_THI_STEP;
+    double hp_hi = h_at(m, mode, reading, thR, b);
+    double hn_lo = h_at(m, mode, reading, thR, -b);
+    int bp = brackets(hp_lo, hp_hi);
+    int bn = brackets(hn_lo, hn_hi);
+    double rp = 0.0, rn = 0.0;
+    if (bp) rp = bisect_thi(m, mode, reading, thR, a, b, hp_lo);
+    if (bn) rn = bisect_thi(m, mode, reading, thR, -b, -a, hn_lo);
+    if (bp && bn) {
+      *thI = (fabs(rn) < fabs(rp)) ? rn : rp;
+      return 0;
+    }
+    if (bp) { *thI = rp; return 0; }
+    if (bn) { *thI = rn; return 0; }
+    hp_lo = hp_hi;
+    hn_hi = hn_lo;
+  }
+  return 1;
+}
+
+int orc_theta_imag(const double *cls, int mode, int reading, double thR,
+                   double *thI) {
+  medium_t m;
+  load_medium(cls, &m);
+  return theta_imag(&m, mode, reading, thR, thI);
+}
+
+static double wrap_pi(double a) {
+  /* into (-pi, pi] */
+  while (a > ORC_PI) a -= 2.0 * ORC_PI;
+  while (a <= -ORC_PI) a += 2.0 * ORC_PI;
+  return a;
+}
+
+typedef struct {
+  double thR, thI, psi;
+  int ok;
+} sample_t;
+
+/* the theta_R sweep: M samples at (j + 1/2) * 2 pi / M */
+static void sweep(const medium_t *m, int mode, int reading, int M,
+                  sample_t *tab) {
+  for (int j = 0; j < M; ++j) {
+    double thR = (j + 0.5) * (2.0 * ORC_PI / M);
+    double thI = 0.0;
+    tab[j].thR = thR;
+    tab[j].ok = 0;
+    if (theta_imag(m, mode, reading, thR, &thI) != 0) continue;
+    eval_t e;
+    energy_velocity(m, mode, reading, thR, thI, &e);
+    double psi = ray_angle_local(&e);
+    if (!isfinite(psi)) continue;
+    tab[j].thI = thI;
+    tab[j].psi = psi;
+    tab[j].ok = 1;
+  }
+}
+
+typedef struct {
+  double thR, thI, V, A, Q, r1, r3, res;
+} entry_t;
+
+/* O-6: ray quantities from the homogeneous complex energy velocity (eqs 10-11) */
+static void ray_quantities(const eval_t *e, entry_t *out) {
+  double r1 = creal(e->v1), r3 = creal(e->v3);
+  double i1 = cimag(e->v1), i3 = cimag(e->v3);
+  double vr = sqrt(r1 * r1 + r3 * r3);
+  double u1 = r1 / vr, u3 = r3 / vr;   /* ray direction */
+  double vi = i1 * u1 + i3 * u3;       /* signed v^I along the ray */
+  double s = vr * vr + vi * vi;
+  out->V = s / vr;
+  out->A = -vi / s;
+  out->Q = (vi == 0.0) ? INFINITY : -(vr * vr - vi * vi) / (2.0 * vr * vi);
+  out->r1 = u1;
+  out->r3 = u3;
+}
+
+/* evaluate the full solution at theta_R: inner root, velocity, quantities */
+static int solution_at(const medium_t *m, int mode, int reading, double thR,
+                       double psi_star, entry_t *out) {
+  double thI;
+  if (theta_imag(m, mode, reading, thR, &thI) != 0) return 1;
+  eval_t e;
+  energy_velocity(m, mode, reading, thR, thI, &e);
+  ray_quantities(&e, out);
+  out->thR = thR;
+  out->thI = thI;
+  double h = mode_elastic(m, mode) ? 0.0 : homog_residual(&e);
+  double dpsi = wrap_pi(ray_angle_local(&e) - psi_star);
+  out->res = fmax(fabs(h), fabs(dpsi));
+  return 0;
+}
+
+static double ang_dist(double a, double b) { return fabs(wrap_pi(a - b)); }
+
+/* solve one target local ray angle psi_star from a sweep table */
+static int solve_direction(const medium_t *m, int mode, int reading, int M,
+                           const sample_t *tab, double psi_star,
+                           entry_t *best) {
+  int found = 0, ill = 0;
+  for (int j = 0; j < M; ++j) {
+    const sample_t *sa = &tab[j];
+    const sample_t *sb = &tab[(j + 1) % M];
+    if (!sa->ok || !sb->ok) continue;
+    double ta = sa->thR;
+    double tb = sb->thR + (j == M - 1 ? 2.0 * ORC_PI : 0.0);
+    double fa = wrap_pi(sa->psi - psi_star);
+    double fb = wrap_pi(sb->psi - psi_star);
+    if (fabs(fb - fa) >= ORC_PI) continue; /* the +-pi seam, not a crossing */
+    if (!brackets(fa, fb)) continue;
+    /* bisection on theta_R; every trial re-solves theta_I */
+    double lo = ta, hi = tb;
+    int neg_lo = fa < 0.0, failed = 0;
+    for (int it = 0; it < 200 && hi - lo > ORC_THR_TOL; ++it) {
+      double mid = 0.5 * (lo + hi);
+      double thI;
+      if (theta_imag(m, mode, reading, mid, &thI) != 0) { failed = 1; break; }
+      eval_t e;
+      energy_velocity(m, mode, reading, mid, thI, &e);
+      double fm = wrap_pi(ray_angle_local(&e) - psi_star);
+      if ((fm < 0.0) == neg_lo) lo = mid; else hi = mid;
+    }
+    if (failed) continue;
+    double thR = 0.5 * (lo + hi);
+    if (thR >= 2.0 * ORC_PI) thR -= 2.0 * ORC_PI;
+    entry_t cand;
+    if (solution_at(m, mode, reading, thR, psi_star, &cand) != 0) continue;
+    double slope = (fb - fa) / (tb - ta);
+    int cand_ill = fabs(slope) < ORC_ILL_SLOPE;
+    int take = 0;
+    if (!found) {
+      take = 1;
+    } else if (cand.V > best->V * (1.0 + ORC_TIE_REL)) {
+      take = 1;
+    } else if (fabs(cand.V - best->V) <= ORC_TIE_REL * best->V &&
+               ang_dist(cand.thR, psi_star) < ang_dist(best->thR, psi_star)) {
+      take = 1;
+    }
+    if (take) {
+      *best = cand;
+      ill = cand_ill;
+      found = 1;
+    }
+  }
+  if (!found) return ORC_ST_NO_BRACKET;
+  return ill ? ORC_ST_ILL : ORC_ST_OK;
+}
+
+static void rotate_to_global(double tilt, double l1, double l3, double *gx,
+                             double *gz) {
+  /* x = x' cos t0 + z' sin t0 ;  z = -x' sin t0 + z' cos t0  (eq 36) */
+  *gx = l1 * cos(tilt) + l3 * sin(tilt);
+  *gz = -l1 * sin(tilt) + l3 * cos(tilt);
+}
+
+static void write_entry(double *fields, long stride, long idx,
+                        const entry_t *e, double tilt) {
+  double gx, gz;
+  rotate_to_global(tilt, e->r1, e->r3, &gx, &gz);
+  fields[F_V * stride + idx] = e->V;
+  fields[F_A * stride + idx] = e->A;
+  fields[F_Q * stride + idx] = e->Q;
+  fields[F_RX * stride + idx] = gx;
+  fields[F_RZ * stride + idx] = gz;
+  fields[F_THR * stride + idx] = e->thR;
+  fields[F_THI * stride + idx] = e->thI;
+  fields[F_RES * stride + idx] = e->res;
+}
+
+static void write_invalid(double *fields, long stride, long idx) {
+  for (int f = 0; f < ORC_NF; ++f) fields[f * stride + idx] = NAN;
+}
+
+/* Solve a single target local ray angle (test helper).  out = 8 fields in
+ * the F_* order with the direction left in the local frame; returns status. */
+int orc_solve(const double *cls, int mode, int reading, int n_sweep,
+              double psi_star_local, double *out) {
+  medium_t m;
+  load_medium(cls, &m);
+  sample_t *tab = (sample_t *)malloc(sizeof(sample_t) * (size_t)n_sweep);
+  if (!tab) return -1;
+  sweep(&m, mode, reading, n_sweep, tab);
+  entry_t e;
+  int st = solve_direction(&m, mode, reading, n_sweep, tab, psi_star_local, &e);
+  free(tab);
+  if (st & ORC_ST_NO_BRACKET) {
+    for (int f = 0; f < ORC_NF; ++f) out[f] = NAN;
+    return st;
+  }
+  out[F_V] = e.V;
+  out[F_A] = e.A;
+  out[F_Q] = e.Q;
+  out[F_RX] = e.r1;
+  out[F_RZ] = e.r3;
+  out[F_THR] = e.thR;
+  out[F_THI] = e.thI;
+  out[F_RES] = e.res;
+  return st;
+}
+
+/* Sweep table export for tests: thR, thI, psi, ok per sample. */
+int orc_sweep(const double *cls, int mode, int reading, int n_sweep,
+              double *thR, double *thI, double *psi, int *ok) {
+  medium_t m;
+  load_medium(cls, &m);
+  sample_t *tab = (sample_t *)malloc(sizeof(sample_t) * (size_t)n_sweep);
+  if (!tab) return -1;
+  sweep(&m, mode, reading, n_sweep, tab);
+  for (int j = 0; j < n_sweep; ++j) {
+    thR[j] = tab[j].thR;
+    thI[j] = tab[j].ok ? tab[j].thI : NAN;
+    psi[j] = tab[j].ok ? tab[j].psi : NAN;
+    ok[j] = tab[j].ok;
+  }
+  free(tab);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O-7  the directional cache C(m, k, theta) (eq 26)                        */
+/* ------------------------------------------------------------------------ */
+
+/* fields: [ORC_NF][3 modes][n_classes][n_dirs]; status: [3][n_classes][n_dirs].
+ * Modes outside mode_mask are left untouched. */
+int orc_build_cache_2d(const double *classes, long n_classes, int n_dirs,
+                       unsigned mode_mask, int reading, int n_sweep,
+                       double *fields, int32_t *status) {
+  if (n_dirs <= 0 || (n_dirs & 1) || n_sweep < 8) return 1;
+  long stride = 3L * n_classes * n_dirs;
+  sample_t *tab = (sample_t *)malloc(sizeof(sample_t) * (size_t)n_sweep);
+  if (!tab) return 2;
+  int half = n_dirs / 2;
+  for (int mode = 0; mode < 3; ++mode) {
+    if (!(mode_mask & (1u << mode))) continue;
+    for (long k = 0; k < n_classes; ++k) {
+      const double *cls = classes + 13 * k;
+      medium_t m;
+      load_medium(cls, &m);
+      long base = ((long)mode * n_classes + k) * n_dirs;
+      int fluid = (mode != ORC_QP) && (cls[3] == 0.0 || (mode == ORC_QSH && cls[4] == 0.0));
+      if (fluid) {
+        for (int d = 0; d < n_dirs; ++d) {
+          write_invalid(fields, stride, base + d);
+          status[base + d] = ORC_ST_FLUID;
+        }
+        continue;
+      }
+      sweep(&m, mode, reading, n_sweep, tab);
+      for (int d = 0; d < half; ++d) {
+        double psi_global = d * (2.0 * ORC_PI / n_dirs);
+        double psi_star = wrap_pi(psi_global - m.tilt);
+        entry_t e;
+        int st = solve_direction(&m, mode, reading, n_sweep, tab, psi_star, &e);
+        if (st & ORC_ST_NO_BRACKET) {
+          write_invalid(fields, stride, base + d);
+          write_invalid(fields, stride, base + d + half);
+          status[base + d] = st;
+          status[base + d + half] = st;
+          continue;
+        }
+        if (!(e.A >= 0.0) || !isfinite(e.V) || !(e.V > 0.0)) st |= ORC_ST_NONPHYS;
+        write_entry(fields, stride, base + d, &e, m.tilt);
+        status[base + d] = st;
+        /* centrosymmetric copy: the reversed ray direction has the same
+         * ray quantities; the slowness direction turns by pi */
+        entry_t r = e;
+        r.r1 = -e.r1;
+        r.r3 = -e.r3;
+        r.thR = e.thR + ORC_PI;
+        if (r.thR >= 2.0 * ORC_PI) r.thR -= 2.0 * ORC_PI;
+        write_entry(fields, stride, base + d + half, &r, m.tilt);
+        /* exact negation of the already-rotated direction */
+        fields[F_RX * stride + base + d + half] = -fields[F_RX * stride + base + d];
+        fields[F_RZ * stride + base + d + half] = -fields[F_RZ * stride + base + d];
+        status[base + d + half] = st;
+      }
+    }
+  }
+  free(tab);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O-8  forward star, edge lengths and direction bins (eq 27)               */
+/* ------------------------------------------------------------------------ */
+
+static int gcd_int(int a, int b) {
+  a = abs(a);
+  b = abs(b);
+  while (b) {
+    int t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+/* Offsets o with max(|ox|,|oz|) <= R and gcd(|ox|,|oz|) = 1, ordered by
+ * (oz, ox) ascending.  Returns the count (arrays may be NULL to count). */
+int orc_star_2d(int R, double hx, double hz, int n_dirs, int32_t *ox,
+                int32_t *oz, double *L, int32_t *bin) {
+  int n = 0;
+  for (int z = -R; z <= R; ++z) {
+    for (int x = -R; x <= R; ++x) {
+      if (x == 0 && z == 0) continue;
+      if (gcd_int(x, z) != 1) continue;
+      if (ox) {
+        double dx = x * hx, dz = z * hz;
+        ox[n] = x;
+        oz[n] = z;
+        L[n] = sqrt(dx * dx + dz * dz);
+        double ang = atan2(dx, dz); /* from +z towards +x */
+        long b = lround(ang * n_dirs / (2.0 * ORC_PI));
+        b %= n_dirs;
+        if (b < 0) b += n_dirs;
+        bin[n] = (int32_t)b;
+      }
+      ++n;
+    }
+  }
+  return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O-9 .. O-12  edge weights, Dijkstra, predecessors, t*                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  double key;
+  long node;
+} heap_item;
+
+typedef struct {
+  heap_item *a;
+  long n, cap;
+} heap_t;
+
+static int heap_push(heap_t *h, double key, long node) {
+  if (h->n == h->cap) {
+    long nc = h->cap ? 2 * h->cap : 1024;
+    heap_item *na = (heap_item *)realloc(h->a, sizeof(heap_item) * (size_t)nc);
+    if (!na) return 1;
+    h->a = na;
+    h->cap = nc;
+  }
+  long i = h->n++;
+  h->a[i].key = key;
+  h->a[i].node = node;
+  while (i > 0) {
+    long p = (i - 1) / 2;
+    if (h->a[p].key <= h->a[i].key) break;
+    heap_item t = h->a[p];
+    h->a[p] = h->a[i];
+    h->a[i] = t;
+    i = p;
+  }
+  return 0;
+}
+
+static heap_item heap_pop(heap_t *h) {
+  heap_item top = h->a[0];
+  h->a[0] = h->a[--h->n];
+  long i = 0;
+  for (;;) {
+    long l = 2 * i + 1, r = l + 1, s = i;
+    if (l < h->n && h->a[l].key < h->a[s].key) s = l;
+    if (r < h->n && h->a[r].key < h->a[s].key) s = r;
+    if (s == i) break;
+    heap_item t = h->a[s];
+    h->a[s] = h->a[i];
+    h->a[i] = t;
+    i = s;
+  }
+  return top;
+}
+
+typedef struct {
+  long nx, nz;
+  int n_off;
+  const int32_t *ox, *oz, *bin;
+  const double *L;
+  const int32_t *cls;   /* node -> class */
+  int n_dirs;
+  const double *V, *A;  /* [class][dir] for one mode */
+  const int32_t *st;    /* [class][dir] */
+} graph_t;
+
+static int entry_usable(const graph_t *g, long k, int b) {
+  int32_t s = g->st[k * g->n_dirs + b];
+  return !(s & (ORC_ST_NO_BRACKET | ORC_ST_FLUID | ORC_ST_NONPHYS));
+}
+
+/* eq 29 / eq 30 with endpoint averages (eq 28); field 0 = propagation,
+ * field 1 = attenuation.  Not usable -> +inf. */
+static double edge_weight(const graph_t *g, int field, long i, long j, int o) {
+  long ki = g->cls[i], kj = g->cls[j];
+  int b = g->bin[o];
+  if (!entry_usable(g, ki, b) || !entry_usable(g, kj, b)) return INFINITY;
+  if (field == 0) {
+    double vbar = 0.5 * (g->V[ki * g->n_dirs + b] + g->V[kj * g->n_dirs + b]);
+    return g->L[o] / vbar;
+  }
+  double abar = 0.5 * (g->A[ki * g->n_dirs + b] + g->A[kj * g->n_dirs + b]);
+  return g->L[o] * abar;
+}
+
+/* neighbour j = i + o (in-grid) or -1 */
+static long step(const graph_t *g, long i, int o) {
+  long ix = i % g->nx, iz = i / g->nx;
+  long jx = ix + g->ox[o], jz = iz + g->oz[o];
+  if (jx < 0 || jx >= g->nx || jz < 0 || jz >= g->nz) return -1;
+  return jx + g->nx * jz;
+}
+
+/* textbook Dijkstra with a binary heap and lazy deletion */
+static int dijkstra(const graph_t *g, int field, long src, double *tau) {
+  long n = g->nx * g->nz;
+  for (long i = 0; i < n; ++i) tau[i] = INFINITY;
+  char *done = (char *)calloc((size_t)n, 1);
+  heap_t h = {0, 0, 0};
+  if (!done) return 1;
+  tau[src] = 0.0;
+  if (heap_push(&h, 0.0, src)) { free(done); return 1; }
+  while (h.n > 0) {
+    heap_item it = heap_pop(&h);
+    long u = it.node;
+    if (done[u] || it.key != tau[u]) continue;
+    done[u] = 1;
+    for (int o = 0; o < g->n_off; ++o) {
+      long v = step(g, u, o);
+      if (v < 0 || done[v]) continue;
+      double w = edge_weight(g, field, u, v, o);
+      double cand = tau[u] + w;
+      if (cand < tau[v]) {
+        tau[v] = cand;
+        if (heap_push(&h, cand, v)) { free(done); free(h.a); return 1; }
+      }
+    }
+  }
+  free(done);
+  free(h.a);
+  return 0;
+}
+
+/* Deterministic predecessors: BFS hop counts over tight edges
+ * (tau_i + w_ij == tau_j), then pred_j = the tight i with the smallest
+ * (hop, offset index).  order[] receives the BFS order (n_reached entries). */
+static int predecessors(const graph_t *g, int field, long src,
+                        const double *tau, int32_t *pred, int32_t *hop,
+                        long *order, long *n_reached) {
+  long n = g->nx * g->nz;
+  for (long i = 0; i < n; ++i) {
+    pred[i] = -1;
+    hop[i] = -1;
+  }
+  long head = 0, tail = 0;
+  hop[src] = 0;
+  order[tail++] = src;
+  while (head < tail) {
+    long i = order[head++];
+    for (int o = 0; o < g->n_off; ++o) {
+      long j = step(g, i, o);
+      if (j < 0 || hop[j] >= 0 || !isfinite(tau[j])) continue;
+      double w = edge_weight(g, field, i, j, o);
+      if (tau[i] + w == tau[j]) {
+        hop[j] = hop[i] + 1;
+        order[tail++] = j;
+      }
+    }
+  }
+  *n_reached = tail;
+  /* pull over in-edges i = j - o, i.e. j = i + o */
+  for (long t = 1; t < tail; ++t) {
+    long j = order[t];
+    int best_o = -1;
+    long best_i = -1;
+    for (int o = 0; o < g->n_off; ++o) {
+      /* i = j - o */
+      long jx = j % g->nx, jz = j / g->nx;
+      long ix = jx - g->ox[o], iz = jz - g->oz[o];
+      if (ix < 0 || ix >= g->nx || iz < 0 || iz >= g->nz) continue;
+      long i = ix + g->nx * iz;
+      if (hop[i] < 0) continue;
+      double w = edge_weight(g, field, i, j, o);
+      if (!(tau[i] + w == tau[j])) continue;
+      if (best_i < 0 || hop[i] < hop[best_i]) {
+        best_i = i;
+        best_o = o;
+      }
+      /* equal hop: the lower offset index wins, which the ascending loop
+       * already guarantees */
+    }
+    (void)best_o;
+    pred[j] = (int32_t)best_i;
+  }
+  return 0;
+}
+
+/* Trace one source for one mode on a 2D grid with a class cache.
+ * V, A, st: [n_classes][n_dirs] slices of the chosen mode.
+ * Any output pointer may be NULL.  tstar needs tauR's tree (pred_p). */
+int orc_trace_2d(long nx, long nz, double hx, double hz,
+                 const int32_t *class_id, int R, int n_dirs,
+                 const double *V, const double *A, const int32_t *st,
+                 long src, double *tauR, double *tauI, int32_t *predP,
+                 int32_t *predA, double *tstar, int32_t *hopP,
+                 int32_t *hopA) {
+  long n = nx * nz;
+  if (src < 0 || src >= n || R < 1) return 1;
+  int n_off = orc_star_2d(R, hx, hz, n_dirs, NULL, NULL, NULL, NULL);
+  int32_t *ox = (int32_t *)malloc(sizeof(int32_t) * n_off);
+  int32_t *oz = (int32_t *)malloc(sizeof(int32_t) * n_off);
+  int32_t *bin = (int32_t *)malloc(sizeof(int32_t) * n_off);
+  double *L = (double *)malloc(sizeof(double) * n_off);
+  double *tR = (double *)malloc(sizeof(double) * (size_t)n);
+  double *tI = (double *)malloc(sizeof(double) * (size_t)n);
+  int32_t *pP = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t *pA = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t *hP = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t *hA = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  long *ordP = (long *)malloc(sizeof(long) * (size_t)n);
+  long *ordA = (long *)malloc(sizeof(long) * (size_t)n);
+  int rc = 0;
+  if (!ox || !oz || !bin || !L || !tR || !tI || !pP || !pA || !hP || !hA ||
+      !ordP || !ordA) {
+    rc = 2;
+    goto out;
+  }
+  orc_star_2d(R, hx, hz, n_dirs, ox, oz, L, bin);
+  graph_t g = {nx, nz, n_off, ox, oz, bin, L, class_id, n_dirs, V, A, st};
+  long nrP = 0, nrA = 0;
+  if (dijkstra(&g, 0, src, tR) || dijkstra(&g, 1, src, tI)) { rc = 2; goto out; }
+  predecessors(&g, 0, src, tR, pP, hP, ordP, &nrP);
+  predecessors(&g, 1, src, tI, pA, hA, ordA, &nrA);
+  if (tstar) {
+    /* t*: attenuation folded along the propagation raypath tree, source
+     * outwards in BFS order so each parent is final first */
+    for (long i = 0; i < n; ++i) tstar[i] = INFINITY;
+    tstar[src] = 0.0;
+    for (long t = 1; t < nrP; ++t) {
+      long j = ordP[t];
+      long i = pP[j];
+      /* offset index of j - i */
+      long dx = (j % nx) - (i % nx), dz = (j / nx) - (i / nx);
+      int oo = -1;
+      for (int o = 0; o < n_off; ++o)
+        if (ox[o] == dx && oz[o] == dz) { oo = o; break; }
+      tstar[j] = tstar[i] + edge_weight(&g, 1, i, j, oo);
+    }
+  }
+  if (tauR) memcpy(tauR, tR, sizeof(double) * (size_t)n);
+  if (tauI) memcpy(tauI, tI, sizeof(double) * (size_t)n);
+  if (predP) memcpy(predP, pP, sizeof(int32_t) * (size_t)n);
+  if (predA) memcpy(predA, pA, sizeof(int32_t) * (size_t)n);
+  if (hopP) memcpy(hopP, hP, sizeof(int32_t) * (size_t)n);
+  if (hopA) memcpy(hopA, hA, sizeof(int32_t) * (size_t)n);
+out:
+  free(ox); free(oz); free(bin); free(L); free(tR); free(tI);
+  free(pP); free(pA); free(hP); free(hA); free(ordP); free(ordA);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O-14  uncached (MSPM-style) form: every relaxation re-solves the local   */
+/*       problem at both endpoints for the edge's bin (no cache, no memo)   */
+/* ------------------------------------------------------------------------ */
+
+static int solve_bin_fresh(const double *cls, int mode, int reading,
+                           int n_sweep, int n_dirs, int b, double *V,
+                           double *A) {
+  medium_t m;
+  load_medium(cls, &m);
+  int fluid = (mode != ORC_QP) && (cls[3] == 0.0 || (mode == ORC_QSH && cls[4] == 0.0));
+  if (fluid) return ORC_ST_FLUID;
+  int half = n_dirs / 2;
+  int d = b % half; /* the solved half; b >= half is its centrosymmetric copy */
+  sample_t *tab = (sample_t *)malloc(sizeof(sample_t) * (size_t)n_sweep);
+  if (!tab) return ORC_ST_NO_BRACKET;
+  sweep(&m, mode, reading, n_sweep, tab);
+  double psi_star = wrap_pi(d * (2.0 * ORC_PI / n_dirs) - m.tilt);
+  entry_t e;
+  int st = solve_direction(&m, mode, reading, n_sweep, tab, psi_star, &e);
+  free(tab);
+  if (st & ORC_ST_NO_BRACKET) return st;
+  if (!(e.A >= 0.0) || !isfinite(e.V) || !(e.V > 0.0)) st |= ORC_ST_NONPHYS;
+  *V = e.V;
+  *A = e.A;
+  return st;
+}
+
+/* Dijkstra for one field where each edge weight comes from fresh solves. */
+int orc_trace_uncached_2d(long nx, long nz, double hx, double hz,
+                          const int32_t *class_id, const double *classes,
+                          int R, int n_dirs, int mode, int reading,
+                          int n_sweep, int field, long src, double *tau,
+                          long *n_solves) {
+  long n = nx * nz;
+  if (src < 0 || src >= n) return 1;
+  int n_off = orc_star_2d(R, hx, hz, n_dirs, NULL, NULL, NULL, NULL);
+  int32_t ox[4 * 121], oz[4 * 121], bin[4 * 121];
+  double L[4 * 121];
+  if (n_off > 4 * 121) return 1;
+  orc_star_2d(R, hx, hz, n_dirs, ox, oz, L, bin);
+  for (long i = 0; i < n; ++i) tau[i] = INFINITY;
+  char *done = (char *)calloc((size_t)n, 1);
+  heap_t h = {0, 0, 0};
+  long solves = 0;
+  tau[src] = 0.0;
+  heap_push(&h, 0.0, src);
+  while (h.n > 0) {
+    heap_item it = heap_pop(&h);
+    long u = it.node;
+    if (done[u] || it.key != tau[u]) continue;
+    done[u] = 1;
+    for (int o = 0; o < n_off; ++o) {
+      long ux = u % nx, uz = u / nx;
+      long vx = ux + ox[o], vz = uz + oz[o];
+      if (vx < 0 || vx >= nx || vz < 0 || vz >= nz) continue;
+      long v = vx + nx * vz;
+      if (done[v]) continue;
+      double Vu, Au, Vv, Av;
+      int su = solve_bin_fresh(classes + 13 * class_id[u], mode, reading,
+                               n_sweep, n_dirs, bin[o], &Vu, &Au);
+      int sv = solve_bin_fresh(classes + 13 * class_id[v], mode, reading,
+                               n_sweep, n_dirs, bin[o], &Vv, &Av);
+      solves += 2;
+      int bad = ORC_ST_NO_BRACKET | ORC_ST_FLUID | ORC_ST_NONPHYS;
+      double w;
+      if ((su & bad) || (sv & bad)) w = INFINITY;
+      else if (field == 0) w = L[o] / (0.5 * (Vu + Vv));
+      else w = L[o] * (0.5 * (Au + Av));
+      double cand = tau[u] + w;
+      if (cand < tau[v]) {
+        tau[v] = cand;
+        heap_push(&h, cand, v);
+      }
+    }
+  }
+  free(done);
+  free(h.a);
+  if (n_solves) *n_solves = solves;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O-13  raypath extraction (eqs 33-34), source -> receiver order           */
+/* ------------------------------------------------------------------------ */
+
+/* returns 0 ok, 6 unreachable, 7 cycle, 5 capacity (len set to required) */
+int orc_raypath(const int32_t *pred, long n_nodes, long src, long rcv,
+                int64_t *path, long capacity, long *len) {
+  if (src < 0 || src >= n_nodes || rcv < 0 || rcv >= n_nodes) return 1;
+  long count = 1;
+  long cur = rcv;
+  while (cur != src) {
+    long p = pred[cur];
+    if (p < 0) return 6;
+    if (++count > n_nodes) return 7;
+    cur = p;
+  }
+  *len = count;
+  if (count > capacity) return 5;
+  cur = rcv;
+  for (long q = count - 1; q >= 0; --q) {
+    path[q] = cur;
+    if (q > 0) cur = pred[cur];
+  }
+  return 0;
+}
