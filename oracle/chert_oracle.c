@@ -94,6 +94,7 @@ typedef struct {
   cplx a11, a13, a33, a44, a66;
   int elastic_ps; /* qP/qSV see only real moduli  */
   int elastic_sh; /* qSH sees only real moduli    */
+  int fluid;      /* ideal (visco-)fluid: no shear, a11 = a13 = a33 */
   double tilt;
 } medium_t;
 
@@ -112,11 +113,21 @@ static void load_medium(const double *c, medium_t *m) {
   m->elastic_ps = cimag(m->a11) == 0.0 && cimag(m->a13) == 0.0 &&
                   cimag(m->a33) == 0.0 && cimag(m->a44) == 0.0;
   m->elastic_sh = cimag(m->a44) == 0.0 && cimag(m->a66) == 0.0;
+  m->fluid = m->a44 == 0.0 && m->a66 == 0.0 && m->a11 == m->a13 && m->a11 == m->a33;
   m->tilt = c[11];
 }
 
 static int mode_elastic(const medium_t *m, int mode) {
   return mode == ORC_QSH ? m->elastic_sh : m->elastic_ps;
+}
+
+/* Modes whose homogeneous solution is theta_I = 0 exactly: elastic modes
+ * (the residual is 0/0 there) and qP in an ideal fluid, which is isotropic
+ * (the visco-isotropic simplification of the cache-construction section);
+ * its residual is cubic in theta_I, so a numerical root would only be good
+ * to ~1e-6 rad. */
+static int theta_i_zero(const medium_t *m, int mode) {
+  return mode_elastic(m, mode) || (mode == ORC_QP && m->fluid);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -280,7 +291,7 @@ static int brackets(double ha, double hb) {
  * Returns 0 on success, 1 when there is no root in the bracket. */
 static int theta_imag(const medium_t *m, int mode, int reading, double thR,
                       double *thI) {
-  if (mode_elastic(m, mode)) {
+  if (theta_i_zero(m, mode)) {
     *thI = 0.0;
     return 0;
   }
@@ -378,7 +389,7 @@ static int solution_at(const medium_t *m, int mode, int reading, double thR,
   ray_quantities(&e, out);
   out->thR = thR;
   out->thI = thI;
-  double h = mode_elastic(m, mode) ? 0.0 : homog_residual(&e);
+  double h = theta_i_zero(m, mode) ? 0.0 : homog_residual(&e);
   double dpsi = wrap_pi(ray_angle_local(&e) - psi_star);
   out->res = fmax(fabs(h), fabs(dpsi));
   return 0;

@@ -381,3 +381,19 @@ def test_integer_tilt_equivariance(rock_table):
     for mode in range(3):
         np.testing.assert_allclose(ft[0, mode, 0], f0[0, mode, 0, idx], rtol=1e-11)
         np.testing.assert_allclose(ft[1, mode, 0], f0[1, mode, 0, idx], rtol=1e-9)
+
+
+def test_ideal_fluid_qp_is_homogeneous():
+    """Isotropic (visco-)fluid, no shear stiffness: qP is the visco-isotropic
+    case the cache-construction section allows to simplify, with
+    theta_I = 0 exactly, V = |c|^2 / Re c and A = -Im c / |c|^2; shear modes
+    are flagged FLUID (impassable)."""
+    a, Q = 2.25e6, 1000.0
+    c = O.class_from_thomsen(1500.0, 0.0, 1000.0, 0, 0, 0, 0.4, 0, Q, Q)
+    assert c[0] == c[1] == c[2] and c[3] == c[4] == 0.0
+    f, st = O.build_cache_2d(c)
+    cc = np.sqrt(a * (1 - 1j / Q))
+    assert np.all(st[0, 0] == 0) and np.all(f[6, 0, 0] == 0.0)
+    np.testing.assert_allclose(f[0, 0, 0], abs(cc) ** 2 / cc.real, rtol=1e-13)
+    np.testing.assert_allclose(f[1, 0, 0], -cc.imag / abs(cc) ** 2, rtol=1e-12)
+    assert np.all(st[1:, 0] == O.ST_FLUID)
