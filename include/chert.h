@@ -1,0 +1,237 @@
+/*
+ * chert.h -- C ABI of the MI355X (gfx950) CHERT hot path.
+ *
+ * CHERT (Cached Hamiltonian-Enhanced Ray Tracing) separates two stages
+ * (Method overview; Algorithm 2):
+ *   1. a directional cache C(m, k, theta) of ray velocity, attenuation, Q and
+ *      ray direction per wave mode m, cache class k and sampled ray
+ *      direction theta, filled by solving the g*-Hamiltonian homogeneity
+ *      problem (eqs 2-14, 26);
+ *   2. first-arrival shortest-path traveltimes whose edge costs come from
+ *      cache lookups (eqs 18-19, 22-34): propagation tau_R, attenuation
+ *      tau_I, predecessors, raypaths, and t* along the propagation raypath.
+ *
+ * Conventions shared by every call:
+ *   - Plain C; every call returns an int status (chert_status).  On failure
+ *     chert_last_error() gives a message (thread-local, valid until the next
+ *     failing call on the same thread).
+ *   - Units are SI: metres, seconds, density-normalised moduli in m^2/s^2,
+ *     angles in radians.
+ *   - 2D frame: x to the right, z down (depth).  Angles are measured from +z
+ *     towards +x; the unit vector at angle a is (sin a, cos a) in (x, z).
+ *     A class's symmetry axis is tilted from +z towards +x by `tilt` (eq 36).
+ *   - Node index = ix + nx * iz (x fastest).
+ *   - Pointers named *_dev are device memory, *_host host memory.  The
+ *     library never allocates device memory: outputs and scratch
+ *     ("workspace") are owned by the caller; sizes come from the *_bytes()
+ *     queries.
+ *   - `stream` is a hipStream_t passed as void*.  Kernels are enqueued on it.
+ *     Argument validation happens before anything is enqueued; a validation
+ *     failure leaves every output untouched.
+ */
+#ifndef CHERT_H
+#define CHERT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CHERT_OK = 0,
+  CHERT_ERR_INVALID_ARG = 1,   /* bad sizes, NaN/negative parameters, ... */
+  CHERT_ERR_UNSUPPORTED = 2,   /* valid but not implemented (e.g. dim 3)  */
+  CHERT_ERR_HIP = 3,           /* a HIP runtime call failed               */
+  CHERT_ERR_NO_CONVERGENCE = 4,/* relaxation round cap reached            */
+  CHERT_ERR_CAPACITY = 5,      /* output buffer too small                 */
+  CHERT_ERR_UNREACHABLE = 6,   /* receiver has no predecessor             */
+  CHERT_ERR_CYCLE = 7          /* predecessor chain longer than the grid  */
+} chert_status;
+
+/* wave modes of the sagittal-plane problem */
+typedef enum { CHERT_QP = 0, CHERT_QSV = 1, CHERT_QSH = 2 } chert_mode;
+
+/* Energy-velocity kernel.  MEV (eqs 13-14) is read as the p-gradient of the
+ * g*-Hamiltonian with the eigenvector and its conjugate held fixed:
+ *   v_m = a_mjkl p_l Re(g_j conj(g_k)) / (g^H g).
+ * OEV is eq 12: v_m = a_mjkl p_l g_j g_k / (g^T g). */
+typedef enum { CHERT_KERNEL_MEV = 0, CHERT_KERNEL_OEV = 1 } chert_kernel;
+
+/* Per-entry status bits of the cache. */
+enum {
+  CHERT_ST_OK = 0,
+  CHERT_ST_NO_BRACKET = 1, /* no slowness angle reaches the ray direction   */
+  CHERT_ST_ILL = 2,        /* chosen root where |dpsi/dtheta_R| < 1e-2       */
+  CHERT_ST_FLUID = 4,      /* shear mode in a class without shear stiffness */
+  CHERT_ST_NONPHYS = 8     /* negative attenuation or non-finite velocity   */
+};
+
+/* One cache class: the stored medium of eq 26 (c_ijkl(k), Q_ijkl(k), rho(k))
+ * for a transversely isotropic medium.  Complex moduli follow eq 2:
+ * a_pq = a_pq (1 - i / q_pq); q = INFINITY means elastic. */
+typedef struct chert_class {
+  double a11, a13, a33, a44, a66; /* real density-normalised moduli [m^2/s^2] */
+  double q11, q13, q33, q44, q66; /* quality factors per component          */
+  double rho;                     /* density [kg/m^3]; stored, not used     */
+  double tilt;                    /* symmetry-axis tilt theta_0 (eq 36)      */
+  double azimuth;                 /* phi_0 (eq 35); must be 0 in 2D          */
+} chert_class;
+
+/* Thomsen parameters -> class (exact relations of Thomsen 1986 for the real
+ * moduli; Qp on a11/a13/a33, Qs on a44/a66).  Host, synchronous.
+ * INVALID_ARG on NaN, vp0 <= 0, vs0 < 0, vs0 >= vp0, Q <= 0 or a negative
+ * radicand in the a13 relation (1 + 2 delta < vs0^2/vp0^2). */
+int chert_class_from_thomsen(double vp0, double vs0, double rho, double eps,
+                             double delta, double gamma, double tilt,
+                             double azimuth, double qp, double qs,
+                             chert_class *out);
+
+/* ------------------------------------------------------------------------
+ * Stage 1: the directional cache (eq 26; Algorithm 2, cache construction).
+ * Entry (m, k, d) holds the homogeneous solution (eq 9) whose ray direction
+ * is exactly d * 2 pi / n_dirs (global frame).  The slowness-angle pair
+ * (theta_R, theta_I) is searched as follows: theta_I is the root of the
+ * homogeneity residual nearest 0 in [-30, 30] deg; theta_R is bracketed on a
+ * sweep of n_sweep samples over [0, 2 pi) and refined to the target ray
+ * direction; among several roots (triplications) the largest ray velocity
+ * wins.  Entries d >= n_dirs/2 are the centrosymmetric copies of d - n_dirs/2.
+ * ------------------------------------------------------------------------ */
+typedef struct chert_cache_desc {
+  int32_t dim;        /* 2 (3 is reserved: UNSUPPORTED)                    */
+  int32_t n_dirs;     /* even, >= 4; 360 = 1 degree                         */
+  uint32_t mode_mask; /* bit (1 << chert_mode) per mode to build            */
+  int32_t kernel;     /* chert_kernel                                       */
+  int32_t n_sweep;    /* theta_R sweep samples, >= 16 (1440 = 0.25 degree)  */
+  int32_t reserved;   /* must be 0                                          */
+} chert_cache_desc;
+
+/* Field order of the cache arrays. */
+enum {
+  CHERT_F_V = 0,   /* ray velocity V^Ray (eq 11) [m/s]                   */
+  CHERT_F_A = 1,   /* ray attenuation A^Ray (eq 11) [s/m]                */
+  CHERT_F_Q = 2,   /* ray quality factor Q^Ray (eq 11)                   */
+  CHERT_F_RX = 3,  /* ray direction r_hat, global x                      */
+  CHERT_F_RZ = 4,  /* ray direction r_hat, global z                      */
+  CHERT_F_THR = 5, /* real slowness angle theta_R, local frame [0, 2 pi) */
+  CHERT_F_THI = 6, /* imaginary slowness angle theta_I                   */
+  CHERT_F_RES = 7, /* max(|sin angle(v^R, v^I)|, |ray-direction miss|)   */
+  CHERT_NF = 8
+};
+
+/* Device layout of a cache blob (all offsets in bytes from its start):
+ *   [0, 256)            header: uint32 magic 'CHRT' (0x54524843), uint32
+ *                       version (1), int32 dim, n_dirs, mode_mask, kernel,
+ *                       n_sweep, reserved, int64 n_classes; rest zero.
+ *   fields_offset       double fields[CHERT_NF][3][n_classes][n_dirs]
+ *   status_offset       int32 status[3][n_classes][n_dirs]
+ * Slots of modes outside mode_mask are left as they were.  The blob is
+ * position-independent, so it may be copied to disk and back. */
+typedef struct chert_cache_layout {
+  size_t fields_offset;
+  size_t status_offset;
+  size_t total_bytes;
+} chert_cache_layout;
+
+/* Layout of a cache for n_classes classes.  INVALID_ARG on a bad desc. */
+int chert_cache_layout_of(const chert_cache_desc *d, int64_t n_classes,
+                          chert_cache_layout *out);
+
+/* Scratch needed by chert_build_cache (the theta_R sweep tables). */
+size_t chert_build_cache_workspace_bytes(const chert_cache_desc *d,
+                                         int64_t n_classes);
+
+/* Build the cache for n_classes classes (device array classes_dev) into
+ * cache_dev (layout above).  Asynchronous on `stream`.  Per-entry failures
+ * are reported through the status array, not the return value. */
+int chert_build_cache(const chert_cache_desc *d, const chert_class *classes_dev,
+                      int64_t n_classes, void *cache_dev, void *workspace_dev,
+                      size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Stage 2: traveltime fields (eqs 22, 24, 27-34; Algorithm 2, tracing).
+ * Graph: every node connects to the nodes at the forward-star offsets o with
+ * max(|ox|, |oz|) <= radius and gcd(|ox|, |oz|) = 1, ordered by (oz, ox)
+ * ascending; offsets leaving the grid are dropped.  The edge i -> j with
+ * offset o uses the bin b(o) = round(atan2(ox hx, oz hz) n_dirs / 2 pi) mod
+ * n_dirs and the classes k_i, k_j:
+ *   w_R = L_o / (0.5 (V[k_i][b] + V[k_j][b]))     (eqs 28-29)
+ *   w_I = L_o * (0.5 (A[k_i][b] + A[k_j][b]))     (eqs 28, 30)
+ * with L_o = sqrt((ox hx)^2 + (oz hz)^2) (eq 27); an entry whose status has
+ * NO_BRACKET, FLUID or NONPHYS makes the edge impassable (w = +inf).
+ * tau_R and tau_I are independent first-arrival problems (eqs 24, 31): each
+ * node gets the minimum over paths of the left-to-right FP64 sum of edge
+ * weights (unreachable: +inf).  Predecessors (eq 33) are deterministic: among
+ * the neighbours i with tau_i + w_ij == tau_j the one with the smallest BFS
+ * hop count over such edges, then the smallest offset index, wins.  t* is the
+ * attenuation folded along the propagation raypath: t*_src = 0,
+ * t*_j = t*_pred_p(j) + w_I(pred_p(j) -> j).
+ * ------------------------------------------------------------------------ */
+typedef struct chert_grid {
+  int32_t dim;                 /* 2 (3 is reserved: UNSUPPORTED)           */
+  int32_t radius;              /* forward-star radius R, 1..8              */
+  int64_t nx, nz, ny;          /* nodes per axis; ny must be 1 in 2D       */
+  double hx, hz, hy;           /* node spacing [m]                         */
+  const int32_t *class_id_dev; /* [n_nodes] class of each node, in range   */
+} chert_grid;
+
+/* output selection bits */
+enum {
+  CHERT_OUT_TAU_R = 1,
+  CHERT_OUT_TAU_I = 2,
+  CHERT_OUT_TSTAR = 4,
+  CHERT_OUT_PRED_P = 8,
+  CHERT_OUT_PRED_A = 16
+};
+
+typedef struct chert_trace_opts {
+  uint32_t outputs;   /* CHERT_OUT_* bits.  TSTAR needs TAU_R and PRED_P;
+                         PRED_P needs TAU_R; PRED_A needs TAU_I.           */
+  int32_t tile_x;     /* relaxation tile width in nodes (0 = default 32)   */
+  int32_t tile_z;     /* relaxation tile height in nodes (0 = default 16)  */
+  int32_t max_rounds; /* cap on relaxation rounds per phase (0 = default)  */
+} chert_trace_opts;
+
+/* Scratch needed by chert_trace_field for these arguments. */
+size_t chert_trace_workspace_bytes(const chert_cache_desc *d, int64_t n_classes,
+                                   const chert_grid *g, int32_t n_src,
+                                   const chert_trace_opts *o);
+
+/* Trace n_src sources (host array of node indices) for one mode, reading
+ * edge costs from `cache_dev` (built by chert_build_cache or imported with
+ * the documented layout).  Outputs are device arrays [n_src][n_nodes]; the
+ * ones not selected in o->outputs may be NULL.  Enqueues on `stream` and
+ * returns after the relaxation has converged (the call synchronises the
+ * stream to test for termination).  NO_CONVERGENCE if a phase reaches
+ * max_rounds (outputs then hold a valid upper bound). */
+int chert_trace_field(const chert_cache_desc *d, const void *cache_dev,
+                      int64_t n_classes, const chert_grid *g, int32_t mode,
+                      const int64_t *src_nodes_host, int32_t n_src,
+                      const chert_trace_opts *o, double *tau_r_dev,
+                      double *tau_i_dev, double *tstar_dev,
+                      int32_t *pred_p_dev, int32_t *pred_a_dev,
+                      void *workspace_dev, size_t workspace_bytes,
+                      void *stream);
+
+/* Raypath (eqs 25, 33-34): follow pred from rcv back to src and write the
+ * node sequence src ... rcv into path_out.  Host, synchronous.
+ * *path_len receives the length (also on CAPACITY, so the caller can retry).
+ * UNREACHABLE if a node on the way has pred -1; CYCLE if the chain is longer
+ * than n_nodes; INVALID_ARG on out-of-range indices. */
+int chert_extract_raypath(const int32_t *pred_host, int64_t n_nodes,
+                          int64_t src, int64_t rcv, int64_t *path_out,
+                          int64_t capacity, int64_t *path_len);
+
+/* Forward-star offsets, lengths and bins as used by chert_trace_field
+ * (host, synchronous).  Returns the number of offsets, or -1 on bad args;
+ * arrays may be NULL to count only. */
+int chert_star_2d(int32_t radius, double hx, double hz, int32_t n_dirs,
+                  int32_t *ox, int32_t *oz, double *len, int32_t *bin);
+
+const char *chert_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHERT_H */

@@ -1,0 +1,245 @@
+"""Python binding of the CHERT C ABI (include/chert.h) for MI355X.
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library ``libchert.so`` built from ``csrc/``.  PyTorch provides device memory
+(tensors) and the stream.  Importing this module does not need a GPU; calling
+a device entry point does, and there is no CPU fallback: a missing library
+raises ``ChertError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchert.so")
+
+CHERT_OK = 0
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "HIP",
+                4: "NO_CONVERGENCE", 5: "CAPACITY", 6: "UNREACHABLE", 7: "CYCLE"}
+QP, QSV, QSH = 0, 1, 2
+KERNEL_MEV, KERNEL_OEV = 0, 1
+ST_OK, ST_NO_BRACKET, ST_ILL, ST_FLUID, ST_NONPHYS = 0, 1, 2, 4, 8
+FIELDS = ("V", "A", "Q", "rx", "rz", "thR", "thI", "res")
+NF = len(FIELDS)
+OUT_TAU_R, OUT_TAU_I, OUT_TSTAR, OUT_PRED_P, OUT_PRED_A = 1, 2, 4, 8, 16
+OUT_ALL = 31
+
+EXPORTS = (
+    "chert_class_from_thomsen", "chert_cache_layout_of",
+    "chert_build_cache_workspace_bytes", "chert_build_cache",
+    "chert_trace_workspace_bytes", "chert_trace_field",
+    "chert_extract_raypath", "chert_star_2d", "chert_last_error",
+)
+
+
+class ChertError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class ChertClass(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "a11", "a13", "a33", "a44", "a66", "q11", "q13", "q33", "q44", "q66",
+        "rho", "tilt", "azimuth")]
+
+    def as_array(self):
+        return np.array([getattr(self, n) for n, _ in self._fields_])
+
+
+class CacheDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n_dirs", ctypes.c_int32),
+                ("mode_mask", ctypes.c_uint32), ("kernel", ctypes.c_int32),
+                ("n_sweep", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class CacheLayout(ctypes.Structure):
+    _fields_ = [("fields_offset", ctypes.c_size_t), ("status_offset", ctypes.c_size_t),
+                ("total_bytes", ctypes.c_size_t)]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("radius", ctypes.c_int32),
+                ("nx", ctypes.c_int64), ("nz", ctypes.c_int64), ("ny", ctypes.c_int64),
+                ("hx", ctypes.c_double), ("hz", ctypes.c_double), ("hy", ctypes.c_double),
+                ("class_id_dev", ctypes.c_void_p)]
+
+
+class TraceOpts(ctypes.Structure):
+    _fields_ = [("outputs", ctypes.c_uint32), ("tile_x", ctypes.c_int32),
+                ("tile_z", ctypes.c_int32), ("max_rounds", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libchert.so (after torch, so the HIP runtime is shared)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ChertError(2, f"HIP library not built: {LIB_PATH} "
+                                "(run __graft_entry__.build())")
+        try:
+            import torch  # noqa: F401  (loads the HIP runtime the library links)
+        except ImportError:
+            pass
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, sz, d = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                              ctypes.c_size_t, ctypes.c_double)
+        L.chert_last_error.restype = ctypes.c_char_p
+        L.chert_class_from_thomsen.argtypes = [d] * 10 + [P]
+        L.chert_cache_layout_of.argtypes = [P, i64, P]
+        L.chert_build_cache_workspace_bytes.argtypes = [P, i64]
+        L.chert_build_cache_workspace_bytes.restype = sz
+        L.chert_build_cache.argtypes = [P, P, i64, P, P, sz, P]
+        L.chert_trace_workspace_bytes.argtypes = [P, i64, P, i32, P]
+        L.chert_trace_workspace_bytes.restype = sz
+        L.chert_trace_field.argtypes = [P, P, i64, P, i32, P, i32, P, P, P, P, P, P, P, sz, P]
+        L.chert_extract_raypath.argtypes = [P, i64, i64, i64, P, i64, P]
+        L.chert_star_2d.argtypes = [i32, d, d, i32, P, P, P, P]
+        _lib = L
+    return _lib
+
+
+def chert_last_error() -> str:
+    return lib().chert_last_error().decode()
+
+
+def _check(rc):
+    if rc != CHERT_OK:
+        raise ChertError(rc, chert_last_error())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------- host calls --
+
+def chert_class_from_thomsen(vp0, vs0, rho, eps, delta, gamma, tilt, azimuth, qp, qs):
+    out = ChertClass()
+    _check(lib().chert_class_from_thomsen(vp0, vs0, rho, eps, delta, gamma, tilt,
+                                          azimuth, qp, qs, ctypes.byref(out)))
+    return out
+
+
+def cache_desc(n_dirs=360, modes=(QP, QSV, QSH), kernel=KERNEL_MEV, n_sweep=1440, dim=2):
+    mask = 0
+    for m in modes:
+        mask |= 1 << m
+    return CacheDesc(dim, n_dirs, mask, kernel, n_sweep, 0)
+
+
+def chert_cache_layout_of(desc, n_classes):
+    out = CacheLayout()
+    _check(lib().chert_cache_layout_of(ctypes.byref(desc), n_classes, ctypes.byref(out)))
+    return out
+
+
+def chert_build_cache_workspace_bytes(desc, n_classes):
+    return int(lib().chert_build_cache_workspace_bytes(ctypes.byref(desc), n_classes))
+
+
+def chert_star_2d(radius, hx, hz, n_dirs=360):
+    n = lib().chert_star_2d(radius, hx, hz, n_dirs, None, None, None, None)
+    if n < 0:
+        raise ChertError(1, chert_last_error())
+    ox = np.zeros(n, np.int32)
+    oz = np.zeros(n, np.int32)
+    L = np.zeros(n)
+    b = np.zeros(n, np.int32)
+    lib().chert_star_2d(radius, hx, hz, n_dirs, ox.ctypes.data, oz.ctypes.data,
+                        L.ctypes.data, b.ctypes.data)
+    return ox, oz, L, b
+
+
+def chert_extract_raypath(pred, src, rcv, capacity=None):
+    """pred: host int32 array (numpy or CPU tensor).  Returns int64 path."""
+    p = np.ascontiguousarray(np.asarray(pred), dtype=np.int32)
+    n = p.size
+    cap = n if capacity is None else capacity
+    out = np.zeros(max(cap, 1), np.int64)
+    ln = ctypes.c_int64(0)
+    _check(lib().chert_extract_raypath(p.ctypes.data, n, src, rcv, out.ctypes.data, cap,
+                                       ctypes.byref(ln)))
+    return out[: ln.value].copy()
+
+
+def raypath_length(pred, src, rcv):
+    """Required capacity (the CAPACITY path of chert_extract_raypath)."""
+    p = np.ascontiguousarray(np.asarray(pred), dtype=np.int32)
+    ln = ctypes.c_int64(0)
+    rc = lib().chert_extract_raypath(p.ctypes.data, p.size, src, rcv, None, 0, ctypes.byref(ln))
+    if rc not in (CHERT_OK, 5):
+        _check(rc)
+    return ln.value
+
+
+# ----------------------------------------------------------- device calls --
+
+def chert_build_cache(desc, classes_dev, n_classes, cache_dev, workspace_dev, stream=None):
+    """classes_dev: float64 device tensor [K, 13]; cache_dev: uint8 device
+    tensor of the layout's total_bytes; workspace_dev: uint8 device tensor."""
+    ws = workspace_dev.numel() * workspace_dev.element_size() if workspace_dev is not None else 0
+    _check(lib().chert_build_cache(ctypes.byref(desc), _ptr(classes_dev), n_classes,
+                                   _ptr(cache_dev), _ptr(workspace_dev), ws, _stream(stream)))
+
+
+def make_grid(nx, nz, hx, hz, radius, class_id_dev):
+    g = Grid(2, radius, nx, nz, 1, hx, hz, 0.0, class_id_dev.data_ptr())
+    g._keep = class_id_dev  # the struct holds a raw pointer
+    return g
+
+
+def trace_opts(outputs=OUT_ALL, tile_x=0, tile_z=0, max_rounds=0):
+    return TraceOpts(outputs, tile_x, tile_z, max_rounds)
+
+
+def chert_trace_workspace_bytes(desc, n_classes, grid, n_src, opts):
+    return int(lib().chert_trace_workspace_bytes(ctypes.byref(desc), n_classes,
+                                                 ctypes.byref(grid), n_src, ctypes.byref(opts)))
+
+
+def chert_trace_field(desc, cache_dev, n_classes, grid, mode, src_nodes: Sequence[int], opts,
+                      tau_r=None, tau_i=None, tstar=None, pred_p=None, pred_a=None,
+                      workspace_dev=None, stream=None):
+    src = np.ascontiguousarray(np.asarray(src_nodes, dtype=np.int64).reshape(-1))
+    ws = workspace_dev.numel() * workspace_dev.element_size() if workspace_dev is not None else 0
+    _check(lib().chert_trace_field(
+        ctypes.byref(desc), _ptr(cache_dev), n_classes, ctypes.byref(grid), mode,
+        src.ctypes.data, int(src.size), ctypes.byref(opts), _ptr(tau_r), _ptr(tau_i),
+        _ptr(tstar), _ptr(pred_p), _ptr(pred_a), _ptr(workspace_dev), ws, _stream(stream)))
+
+
+# ------------------------------------------------------------ cache views --
+
+def cache_views(cache_dev, desc, n_classes):
+    """(fields [NF][3][K][n_dirs] float64, status [3][K][n_dirs] int32) views
+    into a cache blob tensor, following the documented layout."""
+    lay = chert_cache_layout_of(desc, n_classes)
+    n = 3 * n_classes * desc.n_dirs
+    f = cache_dev[lay.fields_offset: lay.fields_offset + NF * n * 8]
+    s = cache_dev[lay.status_offset: lay.status_offset + n * 4]
+    return (f.view(dtype=_torch().float64).view(NF, 3, n_classes, desc.n_dirs),
+            s.view(dtype=_torch().int32).view(3, n_classes, desc.n_dirs))
+
+
+def _torch():
+    import torch
+    return torch

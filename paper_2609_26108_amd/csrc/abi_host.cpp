@@ -1,0 +1,147 @@
+// Host-only entry points of the C ABI: error reporting, the constitutive
+// step, cache layout, forward-star geometry and raypath extraction.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "chert.h"
+#include "chert_internal.h"
+
+namespace chert {
+
+static thread_local char g_err[512] = "";
+
+int fail(int code, const char* msg) {
+  snprintf(g_err, sizeof(g_err), "%s", msg ? msg : "");
+  return code;
+}
+
+static int gcd_i(int a, int b) {
+  a = abs(a);
+  b = abs(b);
+  while (b) {
+    int t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+int star_2d(int R, double hx, double hz, int n_dirs, int32_t* ox, int32_t* oz, double* L,
+            int32_t* bin) {
+  int n = 0;
+  for (int z = -R; z <= R; ++z) {
+    for (int x = -R; x <= R; ++x) {
+      if ((x == 0 && z == 0) || gcd_i(x, z) != 1) continue;
+      if (ox) {
+        double dx = x * hx, dz = z * hz;
+        ox[n] = x;
+        oz[n] = z;
+        L[n] = sqrt(dx * dx + dz * dz);  // eq 27, IEEE sqrt
+        long b = lround(atan2(dx, dz) * n_dirs / (2.0 * M_PI));
+        b %= n_dirs;
+        if (b < 0) b += n_dirs;
+        bin[n] = (int32_t)b;
+      }
+      ++n;
+    }
+  }
+  return n;
+}
+
+}  // namespace chert
+
+using namespace chert;
+
+extern "C" const char* chert_last_error(void) { return g_err; }
+
+extern "C" int chert_class_from_thomsen(double vp0, double vs0, double rho, double eps,
+                                        double delta, double gamma, double tilt,
+                                        double azimuth, double qp, double qs,
+                                        chert_class* out) {
+  if (!out) return fail(CHERT_ERR_INVALID_ARG, "null output");
+  double v[] = {vp0, vs0, rho, eps, delta, gamma, tilt, azimuth, qp, qs};
+  for (double x : v)
+    if (isnan(x)) return fail(CHERT_ERR_INVALID_ARG, "NaN Thomsen parameter");
+  if (!(vp0 > 0.0) || vs0 < 0.0 || !(vs0 < vp0))
+    return fail(CHERT_ERR_INVALID_ARG, "need vp0 > vs0 >= 0");
+  if (!(qp > 0.0) || !(qs > 0.0)) return fail(CHERT_ERR_INVALID_ARG, "Q must be positive");
+  // exact Thomsen (1986) relations for the real moduli
+  double a33 = vp0 * vp0;
+  double a44 = vs0 * vs0;
+  double rad = 2.0 * delta * a33 * (a33 - a44) + (a33 - a44) * (a33 - a44);
+  if (!(rad >= 0.0)) return fail(CHERT_ERR_INVALID_ARG, "negative a13 radicand");
+  out->a11 = a33 * (1.0 + 2.0 * eps);
+  out->a13 = sqrt(rad) - a44;
+  out->a33 = a33;
+  out->a44 = a44;
+  out->a66 = a44 * (1.0 + 2.0 * gamma);
+  out->q11 = out->q13 = out->q33 = qp;
+  out->q44 = out->q66 = qs;
+  out->rho = rho;
+  out->tilt = tilt;
+  out->azimuth = azimuth;
+  return CHERT_OK;
+}
+
+extern "C" int chert_cache_layout_of(const chert_cache_desc* d, int64_t n_classes,
+                                     chert_cache_layout* out) {
+  if (!d || !out) return fail(CHERT_ERR_INVALID_ARG, "null desc or output");
+  if (d->dim == 3) return fail(CHERT_ERR_UNSUPPORTED, "3D caches are not built yet");
+  if (d->dim != 2) return fail(CHERT_ERR_INVALID_ARG, "dim must be 2");
+  if (d->n_dirs < 4 || (d->n_dirs & 1)) return fail(CHERT_ERR_INVALID_ARG, "n_dirs must be even, >= 4");
+  if ((d->mode_mask & ~7u) != 0) return fail(CHERT_ERR_INVALID_ARG, "bad mode mask");
+  if (d->kernel != CHERT_KERNEL_MEV && d->kernel != CHERT_KERNEL_OEV)
+    return fail(CHERT_ERR_INVALID_ARG, "bad kernel");
+  if (d->n_sweep < 16) return fail(CHERT_ERR_INVALID_ARG, "n_sweep must be >= 16");
+  if (d->reserved != 0) return fail(CHERT_ERR_INVALID_ARG, "reserved must be 0");
+  if (n_classes <= 0) return fail(CHERT_ERR_INVALID_ARG, "n_classes must be positive");
+  size_t entries = (size_t)3 * (size_t)n_classes * (size_t)d->n_dirs;
+  out->fields_offset = kHeaderBytes;
+  out->status_offset = kHeaderBytes + entries * CHERT_NF * sizeof(double);
+  size_t end = out->status_offset + entries * sizeof(int32_t);
+  out->total_bytes = (end + 255) & ~(size_t)255;
+  return CHERT_OK;
+}
+
+extern "C" int chert_star_2d(int32_t radius, double hx, double hz, int32_t n_dirs,
+                             int32_t* ox, int32_t* oz, double* len, int32_t* bin) {
+  if (radius < 1 || radius > kMaxRadius || !(hx > 0.0) || !(hz > 0.0) || n_dirs < 4) {
+    fail(CHERT_ERR_INVALID_ARG, "bad star arguments");
+    return -1;
+  }
+  if (ox && (!oz || !len || !bin)) {
+    fail(CHERT_ERR_INVALID_ARG, "star arrays must all be given");
+    return -1;
+  }
+  return star_2d(radius, hx, hz, n_dirs, ox, oz, len, bin);
+}
+
+extern "C" int chert_extract_raypath(const int32_t* pred_host, int64_t n_nodes, int64_t src,
+                                     int64_t rcv, int64_t* path_out, int64_t capacity,
+                                     int64_t* path_len) {
+  if (!pred_host || !path_len || n_nodes <= 0)
+    return fail(CHERT_ERR_INVALID_ARG, "null pred/path_len or empty grid");
+  if (src < 0 || src >= n_nodes || rcv < 0 || rcv >= n_nodes)
+    return fail(CHERT_ERR_INVALID_ARG, "source or receiver out of range");
+  // eq 33: walk the parent pointers from the receiver back to the source
+  int64_t count = 1;
+  int64_t cur = rcv;
+  while (cur != src) {
+    int64_t p = pred_host[cur];
+    if (p < 0) return fail(CHERT_ERR_UNREACHABLE, "receiver not reachable from source");
+    if (p >= n_nodes) return fail(CHERT_ERR_INVALID_ARG, "predecessor out of range");
+    if (++count > n_nodes) return fail(CHERT_ERR_CYCLE, "predecessor chain has a cycle");
+    cur = p;
+  }
+  *path_len = count;
+  if (count > capacity || !path_out) return fail(CHERT_ERR_CAPACITY, "path buffer too small");
+  // eq 34: list the nodes from the source to the receiver
+  cur = rcv;
+  for (int64_t q = count - 1; q >= 0; --q) {
+    path_out[q] = cur;
+    if (q > 0) cur = pred_host[cur];
+  }
+  return CHERT_OK;
+}

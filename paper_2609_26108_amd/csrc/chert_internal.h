@@ -1,0 +1,26 @@
+// Host-side helpers shared by the library's translation units.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "chert.h"
+
+namespace chert {
+
+constexpr uint32_t kCacheMagic = 0x54524843u;  // 'CHRT'
+constexpr uint32_t kCacheVersion = 1u;
+constexpr size_t kHeaderBytes = 256;
+constexpr int kMaxSweep = 4096;  // sweep table staged in LDS: 64 KiB
+constexpr int kMaxRadius = 8;
+constexpr int kMaxOffsets = 288;  // (2R+1)^2 - 1 bound on |O_R| in 2D for R <= 8
+
+// Record a failure message for chert_last_error() and return the code.
+int fail(int code, const char* msg);
+
+// Forward star of radius R (offsets ordered by (oz, ox) ascending, primitive
+// only), lengths and direction bins.  Returns the count.
+int star_2d(int R, double hx, double hz, int n_dirs, int32_t* ox, int32_t* oz, double* L,
+            int32_t* bin);
+
+}  // namespace chert

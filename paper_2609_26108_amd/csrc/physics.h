@@ -1,0 +1,258 @@
+// Device-side local physics of the CHERT cache builder (gfx950, FP64).
+//
+// Complex energy velocity of a transversely isotropic viscoelastic medium at
+// a complex slowness angle theta_R + i theta_I in the sagittal plane of the
+// local symmetry-axis frame:
+//   complex moduli a = a^R (1 - i/Q)                         (eq 2)
+//   n = (sin z, 0, cos z), z = theta_R + i theta_I           (eq 7)
+//   Christoffel matrix Gamma_jk = a_ijkl n_i n_l, eigenpair (eq 4)
+//   c = sqrt(G), p = n / c                                   (eq 5)
+//   MEV: v_m = a_mjkl p_l Re(g_j conj g_k) / (g^H g)          (eqs 13-14)
+//   OEV: v_m = a_mjkl p_l g_j g_k / (g^T g)                   (eq 12)
+// plus the homogeneity residual (eq 9) and the ray quantities (eqs 10-11).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "chert.h"
+
+namespace chert {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 6.28318530717958647692;
+constexpr double kThiStep = 0.25 * kPi / 180.0;  // outward scan step for theta_I
+constexpr int kThiSteps = 120;                    // 120 * 0.25 deg = 30 deg
+constexpr double kThiTol = 1e-15;
+constexpr double kIllSlope = 1e-2;
+constexpr double kTieRel = 1e-12;
+
+struct cd {
+  double re, im;
+};
+
+__device__ __forceinline__ cd mk(double r, double i) { return cd{r, i}; }
+__device__ __forceinline__ cd operator+(cd a, cd b) { return cd{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cd operator-(cd a, cd b) { return cd{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cd operator*(cd a, cd b) {
+  return cd{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ cd operator*(double s, cd a) { return cd{s * a.re, s * a.im}; }
+__device__ __forceinline__ double norm2(cd a) { return a.re * a.re + a.im * a.im; }
+__device__ __forceinline__ cd conjg(cd a) { return cd{a.re, -a.im}; }
+__device__ __forceinline__ cd cdiv(cd a, cd b) {
+  double d = norm2(b);
+  return cd{(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+// principal square root (Re >= 0), cancellation-free form
+__device__ __forceinline__ cd csqrt_p(cd z) {
+  double ax = fabs(z.re);
+  double r = sqrt(z.re * z.re + z.im * z.im);
+  if (r == 0.0) return cd{0.0, 0.0};
+  double t = sqrt(0.5 * (ax + r));
+  if (z.re >= 0.0) return cd{t, z.im / (2.0 * t)};
+  return cd{fabs(z.im) / (2.0 * t), copysign(t, z.im)};
+}
+
+// complex moduli of one class
+struct Medium {
+  cd a11, a13, a33, a44, a66;
+  bool elastic_ps, elastic_sh;
+  bool fluid;  // no shear stiffness and a11 = a13 = a33: isotropic fluid
+  double tilt;
+};
+
+__device__ __forceinline__ cd complex_modulus(double aR, double q) {
+  double aI = isinf(q) ? 0.0 : aR / q;
+  return cd{aR, -aI};
+}
+
+__device__ __forceinline__ Medium load_medium(const chert_class& c) {
+  Medium m;
+  m.a11 = complex_modulus(c.a11, c.q11);
+  m.a13 = complex_modulus(c.a13, c.q13);
+  m.a33 = complex_modulus(c.a33, c.q33);
+  m.a44 = complex_modulus(c.a44, c.q44);
+  m.a66 = complex_modulus(c.a66, c.q66);
+  m.elastic_ps = m.a11.im == 0.0 && m.a13.im == 0.0 && m.a33.im == 0.0 && m.a44.im == 0.0;
+  m.elastic_sh = m.a44.im == 0.0 && m.a66.im == 0.0;
+  m.fluid = m.a44.re == 0.0 && m.a44.im == 0.0 && m.a66.re == 0.0 && m.a66.im == 0.0 &&
+            m.a11.re == m.a13.re && m.a11.im == m.a13.im && m.a11.re == m.a33.re &&
+            m.a11.im == m.a33.im;
+  m.tilt = c.tilt;
+  return m;
+}
+
+__device__ __forceinline__ bool mode_elastic(const Medium& m, int mode) {
+  return mode == CHERT_QSH ? m.elastic_sh : m.elastic_ps;
+}
+
+// Modes whose homogeneous solution is theta_I = 0 exactly: elastic modes and
+// qP of an isotropic fluid (its residual is cubic in theta_I, so a numerical
+// root would only be determined to ~1e-6 rad).
+__device__ __forceinline__ bool theta_i_zero(const Medium& m, int mode) {
+  return mode_elastic(m, mode) || (mode == CHERT_QP && m.fluid);
+}
+
+// complex energy velocity (local frame): v = (v1, v3)
+struct Vel {
+  cd v1, v3;
+};
+
+__device__ __forceinline__ Vel energy_velocity(const Medium& m, int mode, int kernel,
+                                               double thR, double thI) {
+  double sr, cr;
+  sincos(thR, &sr, &cr);
+  double sh = sinh(thI), ch = cosh(thI);
+  cd n1 = cd{sr * ch, cr * sh};   // sin(z)
+  cd n3 = cd{cr * ch, -sr * sh};  // cos(z)
+  cd n11 = n1 * n1, n33 = n3 * n3;
+  Vel out;
+  if (mode == CHERT_QSH) {
+    cd G = m.a66 * n11 + m.a44 * n33;
+    cd c = csqrt_p(G);
+    cd p1 = cdiv(n1, c), p3 = cdiv(n3, c);
+    out.v1 = m.a66 * p1;
+    out.v3 = m.a44 * p3;
+    return out;
+  }
+  cd G11 = m.a11 * n11 + m.a44 * n33;
+  cd G33 = m.a44 * n11 + m.a33 * n33;
+  cd a1344 = m.a13 + m.a44;
+  cd G13 = a1344 * (n1 * n3);
+  cd mean = 0.5 * (G11 + G33);
+  cd half = 0.5 * (G11 - G33);
+  cd root = csqrt_p(half * half + G13 * G13);
+  cd G = (mode == CHERT_QP) ? mean + root : mean - root;
+  cd ua = G13, ub = G - G11;
+  cd wa = G - G33, wb = G13;
+  double nu = norm2(ua) + norm2(ub);
+  double nw = norm2(wa) + norm2(wb);
+  cd g1 = (nu >= nw) ? ua : wa;
+  cd g3 = (nu >= nw) ? ub : wb;
+  cd c = csqrt_p(G);
+  cd p1 = cdiv(n1, c), p3 = cdiv(n3, c);
+  cd S11, S33, S13;
+  if (kernel == CHERT_KERNEL_OEV) {
+    cd N = g1 * g1 + g3 * g3;
+    S11 = cdiv(g1 * g1, N);
+    S33 = cdiv(g3 * g3, N);
+    S13 = cdiv(g1 * g3, N);
+  } else {
+    double q1 = norm2(g1), q3 = norm2(g3);
+    double N = q1 + q3;
+    S11 = cd{q1 / N, 0.0};
+    S33 = cd{q3 / N, 0.0};
+    S13 = cd{(g1.re * g3.re + g1.im * g3.im) / N, 0.0};
+  }
+  out.v1 = p1 * (m.a11 * S11 + m.a44 * S33) + p3 * (a1344 * S13);
+  out.v3 = p3 * (m.a33 * S33 + m.a44 * S11) + p1 * (a1344 * S13);
+  return out;
+}
+
+// sine of the angle between v^R and v^I (eq 9): zero when collinear
+__device__ __forceinline__ double homog_residual(const Vel& v) {
+  double r1 = v.v1.re, r3 = v.v3.re, i1 = v.v1.im, i3 = v.v3.im;
+  return (r1 * i3 - r3 * i1) / (sqrt(r1 * r1 + r3 * r3) * sqrt(i1 * i1 + i3 * i3));
+}
+
+__device__ __forceinline__ double ray_angle(const Vel& v) { return atan2(v.v1.re, v.v3.re); }
+
+// into (-pi, pi]
+__device__ __forceinline__ double wrap_pi(double a) {
+  if (a > kPi) a -= kTwoPi;
+  else if (a <= -kPi) a += kTwoPi;
+  return a;
+}
+
+__device__ __forceinline__ double h_at(const Medium& m, int mode, int kernel, double thR,
+                                       double thI) {
+  return homog_residual(energy_velocity(m, mode, kernel, thR, thI));
+}
+
+__device__ __forceinline__ bool brackets(double fa, double fb) {
+  if (isnan(fa) || isnan(fb)) return false;
+  return (fa < 0.0) != (fb < 0.0);
+}
+
+// Illinois (modified regula falsi) on a bracket [a, b] of h(thR, .)
+__device__ __noinline__ double refine_thi(const Medium& m, int mode, int kernel, double thR,
+                                          double a, double b, double fa, double fb) {
+  int side = 0;
+  double c = 0.5 * (a + b);
+  for (int it = 0; it < 80; ++it) {
+    double cn = (a * fb - b * fa) / (fb - fa);
+    if (!(cn > fmin(a, b) && cn < fmax(a, b))) cn = 0.5 * (a + b);
+    double fc = h_at(m, mode, kernel, thR, cn);
+    double step = fabs(cn - c);
+    c = cn;
+    if (fc == 0.0) return c;
+    if ((fc < 0.0) == (fa < 0.0)) {
+      a = c;
+      fa = fc;
+      if (side == -1) fb *= 0.5;
+      side = -1;
+    } else {
+      b = c;
+      fb = fc;
+      if (side == 1) fa *= 0.5;
+      side = 1;
+    }
+    if (fabs(b - a) <= kThiTol || step <= 1e-17) break;
+  }
+  return c;
+}
+
+// theta_I(theta_R): root of the homogeneity residual nearest 0 in [-30, 30]
+// deg, found by an outward 0.25-degree scan.  Returns false if none.
+__device__ __noinline__ bool theta_imag(const Medium& m, int mode, int kernel, double thR,
+                                        double* thI) {
+  if (theta_i_zero(m, mode)) {
+    *thI = 0.0;
+    return true;
+  }
+  double h0 = h_at(m, mode, kernel, thR, 0.0);
+  if (h0 == 0.0) {
+    *thI = 0.0;
+    return true;
+  }
+  double hp_lo = h0, hn_hi = h0;
+  for (int k = 0; k < kThiSteps; ++k) {
+    double a = k * kThiStep, b = (k + 1) * kThiStep;
+    double hp_hi = h_at(m, mode, kernel, thR, b);
+    double hn_lo = h_at(m, mode, kernel, thR, -b);
+    bool bp = brackets(hp_lo, hp_hi);
+    bool bn = brackets(hn_lo, hn_hi);
+    if (bp || bn) {
+      double rp = bp ? refine_thi(m, mode, kernel, thR, a, b, hp_lo, hp_hi) : 0.0;
+      double rn = bn ? refine_thi(m, mode, kernel, thR, -b, -a, hn_lo, hn_hi) : 0.0;
+      if (bp && bn) *thI = (fabs(rn) < fabs(rp)) ? rn : rp;
+      else *thI = bp ? rp : rn;
+      return true;
+    }
+    hp_lo = hp_hi;
+    hn_hi = hn_lo;
+  }
+  return false;
+}
+
+struct Entry {
+  double V, A, Q, r1, r3, thR, thI, res;
+};
+
+// ray quantities from a homogeneous complex energy velocity (eqs 10-11)
+__device__ __forceinline__ void ray_quantities(const Vel& v, Entry* e) {
+  double r1 = v.v1.re, r3 = v.v3.re, i1 = v.v1.im, i3 = v.v3.im;
+  double vr = sqrt(r1 * r1 + r3 * r3);
+  double u1 = r1 / vr, u3 = r3 / vr;
+  double vi = i1 * u1 + i3 * u3;
+  double s = vr * vr + vi * vi;
+  e->V = s / vr;
+  e->A = -vi / s;
+  e->Q = (vi == 0.0) ? INFINITY : -(vr * vr - vi * vi) / (2.0 * vr * vi);
+  e->r1 = u1;
+  e->r3 = u3;
+}
+
+}  // namespace chert

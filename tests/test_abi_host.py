@@ -1,0 +1,154 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and exports
+every function include/chert.h declares, the host entry points agree with the
+oracle, and device entry points reject bad arguments before launching."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2609_26108_amd as C
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "chert.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(chert_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 9
+    lib = ctypes.CDLL(C.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(C.EXPORTS) <= set(names)
+
+
+def test_class_from_thomsen_matches_oracle():
+    for L in W.config2().layers + W.config1().layers:
+        a = C.chert_class_from_thomsen(*L.thomsen_args()).as_array()
+        b = O.class_from_thomsen(*L.thomsen_args())
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("args", [
+    (3000.0, 3100.0, 2000, 0.1, 0.0, 0.0, 0, 0, 50, 50),      # vs >= vp
+    (3000.0, 2900.0, 2000, 0.1, -0.45, 0.0, 0, 0, 50, 50),    # negative radicand
+    (3000.0, 1500.0, 2000, 0.1, 0.0, 0.0, 0, 0, 0.0, 50),     # Q <= 0
+    (float("nan"), 1500.0, 2000, 0.1, 0.0, 0.0, 0, 0, 50, 50),
+])
+def test_class_from_thomsen_rejects(args):
+    with pytest.raises(C.ChertError) as e:
+        C.chert_class_from_thomsen(*args)
+    assert e.value.code == 1
+
+
+def test_star_matches_oracle_bitwise():
+    for R in range(1, 9):
+        for hx, hz in [(10.0, 10.0), (5.0, 7.5)]:
+            a = C.chert_star_2d(R, hx, hz)
+            b = O.star_2d(R, hx, hz)
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y)
+
+
+def test_layout():
+    d = C.cache_desc(n_dirs=360, modes=(0, 1, 2))
+    lay = C.chert_cache_layout_of(d, 5)
+    n = 3 * 5 * 360
+    assert lay.fields_offset == 256
+    assert lay.status_offset == 256 + 8 * n * 8
+    assert lay.total_bytes >= lay.status_offset + 4 * n and lay.total_bytes % 256 == 0
+    for bad in [C.cache_desc(n_dirs=359), C.cache_desc(n_sweep=8), C.CacheDesc(2, 360, 8, 0, 1440, 0),
+                C.CacheDesc(2, 360, 1, 5, 1440, 0)]:
+        with pytest.raises(C.ChertError):
+            C.chert_cache_layout_of(bad, 5)
+    with pytest.raises(C.ChertError) as e:
+        C.chert_cache_layout_of(C.cache_desc(dim=3), 5)
+    assert e.value.code == 2
+
+
+def test_raypath_matches_oracle_and_errors():
+    rng = np.random.default_rng(1)
+    nx, nz = 15, 11
+    V = np.concatenate([rng.uniform(2000, 3000, (2, 180))] * 2, 1)
+    A = np.full((2, 360), 1e-4)
+    st = np.zeros((2, 360), np.int32)
+    cid = rng.integers(0, 2, nx * nz).astype(np.int32)
+    r = O.trace_2d(nx, nz, 5.0, 5.0, cid, 3, V, A, st, 7)
+    for rcv in range(nx * nz):
+        p = C.chert_extract_raypath(r["predP"], 7, rcv)
+        rc, q = O.raypath(r["predP"], 7, rcv)
+        assert rc == 0 and np.array_equal(p, q)
+    assert C.raypath_length(r["predP"], 7, nx * nz - 1) == len(
+        C.chert_extract_raypath(r["predP"], 7, nx * nz - 1))
+    with pytest.raises(C.ChertError) as e:
+        C.chert_extract_raypath(r["predP"], 7, nx * nz - 1, capacity=1)
+    assert e.value.code == 5
+    pred = r["predP"].copy()
+    pred[20] = -1
+    with pytest.raises(C.ChertError) as e:
+        C.chert_extract_raypath(pred, 7, 20)
+    assert e.value.code == 6
+    pred = np.full(nx * nz, -1, np.int32)
+    pred[3], pred[4] = 4, 3
+    with pytest.raises(C.ChertError) as e:
+        C.chert_extract_raypath(pred, 7, 3)
+    assert e.value.code == 7
+    with pytest.raises(C.ChertError) as e:
+        C.chert_extract_raypath(pred, 7, nx * nz)
+    assert e.value.code == 1
+
+
+class _FakeTensor:
+    """Stands in for a device tensor in validation-only calls (never
+    dereferenced: validation fails before any launch)."""
+    def __init__(self, n=0):
+        self.n = n
+
+    def data_ptr(self):
+        return 0
+
+    def numel(self):
+        return self.n
+
+    def element_size(self):
+        return 1
+
+
+def test_device_calls_validate_before_launch():
+    d = C.cache_desc(n_dirs=361)
+    with pytest.raises(C.ChertError) as e:
+        C.chert_build_cache(d, _FakeTensor(), 3, _FakeTensor(), _FakeTensor(), stream=0)
+    assert e.value.code == 1
+    d = C.cache_desc()
+    with pytest.raises(C.ChertError) as e:  # null classes / cache
+        C.chert_build_cache(d, _FakeTensor(), 3, _FakeTensor(), _FakeTensor(), stream=0)
+    assert e.value.code == 1
+    g = C.Grid(2, 0, 10, 10, 1, 5.0, 5.0, 0.0, None)
+    o = C.trace_opts()
+    with pytest.raises(C.ChertError) as e:  # radius 0
+        C.chert_trace_field(d, _FakeTensor(), 3, g, 0, [0], o, workspace_dev=_FakeTensor(), stream=0)
+    assert e.value.code == 1
+    assert C.chert_trace_workspace_bytes(d, 3, g, 1, o) == 0
+    g = C.Grid(2, 3, 10, 10, 1, 5.0, 5.0, 0.0, 1234)
+    with pytest.raises(C.ChertError) as e:  # null outputs for the selected mask
+        C.chert_trace_field(d, _FakeTensor(), 3, g, 0, [0], o, workspace_dev=_FakeTensor(), stream=0)
+    assert e.value.code == 1
+    with pytest.raises(C.ChertError) as e:  # source out of range
+        C.chert_trace_field(d, _FakeTensor(), 3, g, 0, [100], o, workspace_dev=_FakeTensor(), stream=0)
+    assert e.value.code == 1
+    o2 = C.trace_opts(outputs=C.OUT_TSTAR)
+    with pytest.raises(C.ChertError):  # t* without its inputs
+        C.chert_trace_field(d, _FakeTensor(), 3, g, 0, [0], o2, workspace_dev=_FakeTensor(), stream=0)
+    g3 = C.Grid(3, 3, 10, 10, 10, 5.0, 5.0, 5.0, 1234)
+    with pytest.raises(C.ChertError) as e:
+        C.chert_trace_field(d, _FakeTensor(), 3, g3, 0, [0], o, workspace_dev=_FakeTensor(), stream=0)
+    assert e.value.code == 2
+    assert C.chert_trace_workspace_bytes(d, 3, g, 1, o) > 0

@@ -1,0 +1,156 @@
+"""GPU parity of the traveltime fields (chert_trace_field) against the
+oracle's Dijkstra.
+
+On an imported (oracle-computed) cache the fields must be bitwise equal
+(tau_R, tau_I, t*) and the predecessors identical: both sides compute the
+minimum over paths of the left-to-right FP64 sum of identical weights.
+End to end (GPU cache -> GPU trace vs oracle cache -> oracle Dijkstra) the bar
+is 1e-9 relative.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+import workloads as W  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import chert_gpu
+    return chert_gpu
+
+
+def C():
+    import paper_2609_26108_amd as mod
+    return mod
+
+
+def oracle_cache(model, modes, n_sweep=1440):
+    cls = np.stack([O.class_from_thomsen(*L.thomsen_args()) for L in model.layers])
+    mask = sum(1 << m for m in modes)
+    f, s = O.build_cache_2d(cls, n_dirs=model.n_dirs, mode_mask=mask, n_sweep=n_sweep)
+    return cls, f, s
+
+
+def assert_fields_equal(g, o, s_idx=0):
+    for key in ("tauR", "tauI", "tstar"):
+        if g[key] is None:
+            continue
+        a, b = g[key][s_idx], o[key]
+        assert np.array_equal(a, b), (key, int(np.sum(a != b)))
+    for key in ("predP", "predA"):
+        if g[key] is None:
+            continue
+        a, b = g[key][s_idx], o[key]
+        assert np.array_equal(a, b), (key, int(np.sum(a != b)))
+
+
+def imported_case(G, model, modes, tile=(0, 0), sources=None, n_sweep=1440):
+    cls, f, s = oracle_cache(model, modes, n_sweep)
+    Cm = C()
+    desc = Cm.cache_desc(n_dirs=model.n_dirs, modes=modes, n_sweep=n_sweep)
+    K = cls.shape[0]
+    cache = G.import_cache(f, s, desc, K)
+    sources = model.sources if sources is None else sources
+    for mode in modes:
+        g = G.trace(cache, desc, K, model.nx, model.nz, model.hx, model.hz, model.radius,
+                    model.class_id, mode, sources, tile_x=tile[0], tile_z=tile[1])
+        for si, src in enumerate(sources):
+            o = O.trace_2d(model.nx, model.nz, model.hx, model.hz, model.class_id,
+                           model.radius, f[0, mode], f[1, mode], s[mode], src)
+            print(f"mode {mode} src {src}: finite {int(np.isfinite(o['tauR']).sum())}", flush=True)
+            assert_fields_equal(g, o, si)
+
+
+def test_imported_cache_small_layered_bitwise(G):
+    m = W.small_layered()
+    imported_case(G, m, (0, 1, 2))
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (16, 4), (32, 16), (64, 16)])
+def test_tile_shapes_give_identical_fields(G, tile):
+    """Determinism across schedules: every tile shape reaches the same bits."""
+    m = W.small_layered(nx=53, nz=29, radius=4, seed=3)
+    imported_case(G, m, (1,), tile=tile)
+
+
+def test_multiple_sources_one_call(G):
+    m = W.small_layered(nx=41, nz=27, radius=2, seed=5)
+    srcs = [0, m.nx * m.nz - 1, 17 + m.nx * 13, 40]
+    imported_case(G, m, (0,), sources=srcs)
+
+
+def test_degenerate_grids(G):
+    """One-row and one-column grids, a 1x1 grid, radius 1 and radius 8."""
+    for nx, nz, R in [(57, 1, 3), (1, 45, 2), (1, 1, 1), (19, 17, 8), (33, 2, 1)]:
+        m = W.small_layered(nx=nx, nz=nz, radius=R, seed=nx + nz)
+        m.sources = [min(m.sources[0], nx * nz - 1)]
+        imported_case(G, m, (0,), n_sweep=360)
+
+
+def test_fluid_region_blocks_shear(G):
+    """A class without shear stiffness: shear-mode edges into it are
+    impassable (tau = inf, pred = -1), qP passes."""
+    m = W.small_layered(nx=30, nz=20, radius=3, seed=11)
+    from workloads import Layer
+    m.layers[0] = Layer(1500.0, 0.0, 1000.0, 0.0, 0.0, 0.0, 0.0, 1000.0, 1000.0)
+    imported_case(G, m, (0, 1), n_sweep=360)
+
+
+def test_end_to_end_config1(G):
+    """Config 1 at full size: GPU cache + GPU trace vs the oracle (1e-9)."""
+    m = W.config1()
+    Cm = C()
+    desc = Cm.cache_desc(n_dirs=360, modes=m.modes)
+    cache = G.build_cache(G.classes_from_layers(m.layers), desc)
+    cls, f, s = oracle_cache(m, m.modes)
+    for mode in m.modes:
+        g = G.trace(cache, desc, 1, m.nx, m.nz, m.hx, m.hz, m.radius, m.class_id, mode, m.sources)
+        o = O.trace_2d(m.nx, m.nz, m.hx, m.hz, m.class_id, m.radius, f[0, mode], f[1, mode],
+                       s[mode], m.sources[0])
+        for key in ("tauR", "tauI", "tstar"):
+            a, b = g[key][0], o[key]
+            fin = np.isfinite(b)
+            assert np.array_equal(np.isfinite(a), fin)
+            rel = np.abs(a[fin] - b[fin]) / np.maximum(np.abs(b[fin]), 1e-300)
+            assert rel.max() <= 1e-9, (key, rel.max())
+
+
+def test_end_to_end_config2_full_size(G):
+    """Config 2 (401 x 201, radius 5, 5 classes, 3 modes) end to end."""
+    m = W.config2()
+    Cm = C()
+    desc = Cm.cache_desc(n_dirs=360, modes=m.modes)
+    cache = G.build_cache(G.classes_from_layers(m.layers), desc)
+    cls, f, s = oracle_cache(m, m.modes)
+    for mode in m.modes:
+        g = G.trace(cache, desc, len(m.layers), m.nx, m.nz, m.hx, m.hz, m.radius, m.class_id,
+                    mode, m.sources)
+        o = O.trace_2d(m.nx, m.nz, m.hx, m.hz, m.class_id, m.radius, f[0, mode], f[1, mode],
+                       s[mode], m.sources[0])
+        for key in ("tauR", "tauI", "tstar"):
+            a, b = g[key][0], o[key]
+            fin = np.isfinite(b)
+            assert np.array_equal(np.isfinite(a), fin)
+            rel = np.abs(a[fin] - b[fin]) / np.maximum(np.abs(b[fin]), 1e-300)
+            print(mode, key, float(rel.max()), flush=True)
+            assert rel.max() <= 1e-9, (key, rel.max())
+
+
+def test_invalid_class_id_reported(G):
+    m = W.small_layered(nx=20, nz=10, radius=2, seed=1)
+    cls, f, s = oracle_cache(m, (0,), n_sweep=360)
+    Cm = C()
+    desc = Cm.cache_desc(n_dirs=360, modes=(0,), n_sweep=360)
+    cache = G.import_cache(f, s, desc, cls.shape[0])
+    cid = m.class_id.copy()
+    cid[3, 4] = 99
+    with pytest.raises(Cm.ChertError) as e:
+        G.trace(cache, desc, cls.shape[0], m.nx, m.nz, m.hx, m.hz, m.radius, cid, 0, m.sources)
+    assert e.value.code == 1

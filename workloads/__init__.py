@@ -1,0 +1,127 @@
+"""Seeded synthetic workloads for the CHERT hot path.
+
+This module only draws model parameters (Thomsen parameters, Q, tilt per
+class, node -> class maps, source positions).  It holds none of the method's
+arithmetic, so both the HIP library's callers and the CPU oracle's tests can
+use it.  Every generator is deterministic for a given seed
+(numpy PCG64 with seed = 26108 * 10 + config number by default).
+
+The configurations stand in for the paper's workloads, which are not
+available: config 1 is a homogeneous TTI block, config 2 the
+layered controlled benchmark, config 3 the structurally complex 2D model.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List
+
+import numpy as np
+
+QP, QSV, QSH = 0, 1, 2
+
+
+@dataclass
+class Layer:
+    vp0: float
+    vs0: float
+    rho: float
+    eps: float
+    delta: float
+    gamma: float
+    tilt: float      # radians
+    qp: float
+    qs: float
+    azimuth: float = 0.0
+
+    def thomsen_args(self):
+        """(vp0, vs0, rho, eps, delta, gamma, tilt, azimuth, qp, qs)"""
+        return (self.vp0, self.vs0, self.rho, self.eps, self.delta, self.gamma,
+                self.tilt, self.azimuth, self.qp, self.qs)
+
+
+@dataclass
+class Model2D:
+    name: str
+    nx: int
+    nz: int
+    hx: float
+    hz: float
+    layers: List[Layer]
+    class_id: np.ndarray          # int32 [nz, nx]
+    sources: List[int]            # node indices ix + nx * iz
+    modes: tuple
+    radius: int
+    n_dirs: int = 360
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_nodes(self):
+        return self.nx * self.nz
+
+
+def seed_for(config: int) -> int:
+    return 26108 * 10 + config
+
+
+def config1() -> Model2D:
+    """Homogeneous viscoelastic TTI, 101 x 101 nodes at 10 m, one class,
+    qP/qSV, radius 4, source at node (50, 50)."""
+    L = Layer(3000.0, 1732.0, 2300.0, 0.20, 0.10, 0.15, math.radians(30.0), 60.0, 40.0)
+    nx = nz = 101
+    cid = np.zeros((nz, nx), np.int32)
+    return Model2D("config1_homogeneous_tti_101x101", nx, nz, 10.0, 10.0, [L], cid,
+                   [50 + nx * 50], (QP, QSV), 4)
+
+
+def _layer_params(rng) -> Layer:
+    vp = rng.uniform(2000.0, 4500.0)
+    vs = vp / rng.uniform(1.6, 2.0)
+    rho = rng.uniform(2000.0, 2600.0)
+    eps = rng.uniform(0.0, 0.3)
+    delta = rng.uniform(-0.1, 0.2)
+    gamma = rng.uniform(0.0, 0.2)
+    tilt = math.radians(rng.uniform(-45.0, 45.0))
+    qp = rng.uniform(30.0, 150.0)
+    return Layer(vp, vs, rho, eps, delta, gamma, tilt, qp, 0.6 * qp)
+
+
+def config2(seed: int = None, nx: int = 401, nz: int = 201, h: float = 5.0) -> Model2D:
+    """5-layer TTI, 401 x 201 nodes at 5 m.  Interfaces at depths 200 k m
+    (k = 1..4, scaled to the model depth) plus seeded sine perturbations
+    (amplitude <= 20 m); per-layer parameters drawn uniformly; qP/qSV/qSH,
+    5 classes, radius 5, one surface source at ix = nx // 2."""
+    rng = np.random.default_rng(seed_for(2) if seed is None else seed)
+    layers = [_layer_params(rng) for _ in range(5)]
+    depth = (nz - 1) * h
+    x = np.arange(nx) * h
+    z = np.arange(nz) * h
+    cid = np.zeros((nz, nx), np.int32)
+    for k in range(1, 5):
+        amp = rng.uniform(0.0, 20.0)
+        lam = rng.uniform(300.0, 2000.0)
+        phi = rng.uniform(0.0, 2 * math.pi)
+        zi = k * depth / 5.0 + amp * np.sin(2 * math.pi * x / lam + phi)
+        cid += (z[:, None] > zi[None, :]).astype(np.int32)
+    return Model2D(f"config2_5layer_tti_{nx}x{nz}", nx, nz, h, h, layers, cid,
+                   [nx // 2], (QP, QSV, QSH), 5)
+
+
+def small_layered(nx=37, nz=23, h=10.0, n_layers=3, seed=7, radius=3, tilt_max=40.0):
+    """Small layered TTI model for fast parity tests (several tiles and a
+    ragged tail at the default tile size)."""
+    rng = np.random.default_rng(seed)
+    layers = []
+    for _ in range(n_layers):
+        L = _layer_params(rng)
+        L.tilt = math.radians(rng.uniform(-tilt_max, tilt_max))
+        layers.append(L)
+    z = np.arange(nz) * h
+    x = np.arange(nx) * h
+    cid = np.zeros((nz, nx), np.int32)
+    for k in range(1, n_layers):
+        zi = k * (nz - 1) * h / n_layers + 2 * h * np.sin(2 * math.pi * x / (nx * h) * (k + 1))
+        cid += (z[:, None] > zi[None, :]).astype(np.int32)
+    src = [int(rng.integers(0, nx)) + nx * int(rng.integers(0, 3))]
+    return Model2D(f"small_layered_{nx}x{nz}", nx, nz, h, h, layers, cid, src,
+                   (QP, QSV, QSH), radius)
