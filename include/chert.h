@@ -189,7 +189,7 @@ typedef struct chert_trace_opts {
   uint32_t outputs;   /* CHERT_OUT_* bits.  TSTAR needs TAU_R and PRED_P;
                          PRED_P needs TAU_R; PRED_A needs TAU_I.           */
   int32_t tile_x;     /* relaxation tile width in nodes (0 = default 32)   */
-  int32_t tile_z;     /* relaxation tile height in nodes (0 = default 16)  */
+  int32_t tile_z;     /* relaxation tile height in nodes (0 = default 32)  */
   int32_t max_rounds; /* cap on relaxation rounds per phase (0 = default)  */
 } chert_trace_opts;
 
@@ -213,6 +213,37 @@ int chert_trace_field(const chert_cache_desc *d, const void *cache_dev,
                       int32_t *pred_p_dev, int32_t *pred_a_dev,
                       void *workspace_dev, size_t workspace_bytes,
                       void *stream);
+
+/* One job of a batched trace: a grid, the cache (and mode) its edge costs
+ * come from, its sources and its outputs ([n_src][nx*nz] device arrays, the
+ * ones not selected in the options may be NULL). */
+typedef struct chert_trace_job {
+  const chert_cache_desc *d;
+  const void *cache_dev;
+  int64_t n_classes;
+  const chert_grid *g;
+  int32_t mode;
+  int32_t n_src;
+  const int64_t *src_nodes_host;
+  double *tau_r_dev;
+  double *tau_i_dev;
+  double *tstar_dev;
+  int32_t *pred_p_dev;
+  int32_t *pred_a_dev;
+} chert_trace_job;
+
+/* Scratch needed by chert_trace_batch (0 on invalid arguments). */
+size_t chert_trace_batch_workspace_bytes(const chert_trace_job *jobs, int32_t n_jobs,
+                                         const chert_trace_opts *o);
+
+/* Many shots on grids of uneven size (Algorithm 2's loops over sources and
+ * modes, run together): every (job, source, field) problem of the batch
+ * advances in the same relaxation launches, so the rounds of all problems
+ * overlap.  Semantics per job are those of chert_trace_field; all jobs must
+ * share one forward-star radius.  At most 65535 problems per batch. */
+int chert_trace_batch(const chert_trace_job *jobs, int32_t n_jobs,
+                      const chert_trace_opts *o, void *workspace_dev,
+                      size_t workspace_bytes, void *stream);
 
 /* Raypath (eqs 25, 33-34): follow pred from rcv back to src and write the
  * node sequence src ... rcv into path_out.  Host, synchronous.

@@ -32,6 +32,7 @@ EXPORTS = (
     "chert_class_from_thomsen", "chert_cache_layout_of",
     "chert_build_cache_workspace_bytes", "chert_build_cache",
     "chert_trace_workspace_bytes", "chert_trace_field",
+    "chert_trace_batch_workspace_bytes", "chert_trace_batch",
     "chert_extract_raypath", "chert_star_2d", "chert_last_error",
 )
 
@@ -69,6 +70,16 @@ class Grid(ctypes.Structure):
                 ("class_id_dev", ctypes.c_void_p)]
 
 
+class TraceJob(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_void_p), ("cache_dev", ctypes.c_void_p),
+                ("n_classes", ctypes.c_int64), ("g", ctypes.c_void_p),
+                ("mode", ctypes.c_int32), ("n_src", ctypes.c_int32),
+                ("src_nodes_host", ctypes.c_void_p),
+                ("tau_r_dev", ctypes.c_void_p), ("tau_i_dev", ctypes.c_void_p),
+                ("tstar_dev", ctypes.c_void_p), ("pred_p_dev", ctypes.c_void_p),
+                ("pred_a_dev", ctypes.c_void_p)]
+
+
 class TraceOpts(ctypes.Structure):
     _fields_ = [("outputs", ctypes.c_uint32), ("tile_x", ctypes.c_int32),
                 ("tile_z", ctypes.c_int32), ("max_rounds", ctypes.c_int32)]
@@ -100,6 +111,9 @@ def lib():
         L.chert_trace_workspace_bytes.argtypes = [P, i64, P, i32, P]
         L.chert_trace_workspace_bytes.restype = sz
         L.chert_trace_field.argtypes = [P, P, i64, P, i32, P, i32, P, P, P, P, P, P, P, sz, P]
+        L.chert_trace_batch_workspace_bytes.argtypes = [P, i32, P]
+        L.chert_trace_batch_workspace_bytes.restype = sz
+        L.chert_trace_batch.argtypes = [P, i32, P, P, sz, P]
         L.chert_extract_raypath.argtypes = [P, i64, i64, i64, P, i64, P]
         L.chert_star_2d.argtypes = [i32, d, d, i32, P, P, P, P]
         _lib = L
@@ -225,6 +239,42 @@ def chert_trace_field(desc, cache_dev, n_classes, grid, mode, src_nodes: Sequenc
         ctypes.byref(desc), _ptr(cache_dev), n_classes, ctypes.byref(grid), mode,
         src.ctypes.data, int(src.size), ctypes.byref(opts), _ptr(tau_r), _ptr(tau_i),
         _ptr(tstar), _ptr(pred_p), _ptr(pred_a), _ptr(workspace_dev), ws, _stream(stream)))
+
+
+class Batch:
+    """Marshals a list of trace jobs into the chert_trace_job array; keeps
+    every referenced structure and array alive for the duration."""
+
+    def __init__(self):
+        self._jobs = []
+        self._keep = []
+
+    def add(self, desc, cache_dev, n_classes, grid, mode, src_nodes, tau_r=None, tau_i=None,
+            tstar=None, pred_p=None, pred_a=None):
+        src = np.ascontiguousarray(np.asarray(src_nodes, dtype=np.int64).reshape(-1))
+        self._keep += [desc, grid, src, cache_dev, tau_r, tau_i, tstar, pred_p, pred_a]
+        ptr = lambda t: None if t is None else t.data_ptr()
+        self._jobs.append(TraceJob(ctypes.addressof(desc), cache_dev.data_ptr(), n_classes,
+                                   ctypes.addressof(grid), mode, int(src.size), src.ctypes.data,
+                                   ptr(tau_r), ptr(tau_i), ptr(tstar), ptr(pred_p), ptr(pred_a)))
+        return self
+
+    def array(self):
+        arr = (TraceJob * len(self._jobs))(*self._jobs)
+        self._keep.append(arr)
+        return arr, len(self._jobs)
+
+
+def chert_trace_batch_workspace_bytes(batch, opts):
+    arr, n = batch.array()
+    return int(lib().chert_trace_batch_workspace_bytes(arr, n, ctypes.byref(opts)))
+
+
+def chert_trace_batch(batch, opts, workspace_dev, stream=None):
+    arr, n = batch.array()
+    ws = workspace_dev.numel() * workspace_dev.element_size() if workspace_dev is not None else 0
+    _check(lib().chert_trace_batch(arr, n, ctypes.byref(opts), _ptr(workspace_dev), ws,
+                                   _stream(stream)))
 
 
 # ------------------------------------------------------------ cache views --

@@ -83,7 +83,7 @@ struct SolveArgs {
 
 // Newton on F = (h, psi - psi*) from the bracket interpolant.  Elastic modes
 // keep theta_I = 0 exactly and solve the 1D direction equation.
-__device__ __noinline__ bool newton_root(const Medium& m, int mode, int kernel,
+__device__ __forceinline__ bool newton_root(const Medium& m, int mode, int kernel,
                                          double psi_star, double ta, double tb,
                                          double ya, double yb, double fa, double fb,
                                          double* xo, double* yo) {
@@ -129,7 +129,7 @@ __device__ __noinline__ bool newton_root(const Medium& m, int mode, int kernel,
 
 // Fallback: nested bisection on theta_R with the inner theta_I solve at every
 // trial point (slow, used only when Newton does not settle).
-__device__ __noinline__ bool bisect_root(const Medium& m, int mode, int kernel,
+__device__ __forceinline__ bool bisect_root(const Medium& m, int mode, int kernel,
                                          double psi_star, double ta, double tb, double fa,
                                          double* xo, double* yo) {
   double lo = ta, hi = tb;
@@ -176,8 +176,60 @@ __device__ __forceinline__ void store_invalid(const SolveArgs& a, int64_t base, 
   a.status[base] = st;
 }
 
+constexpr int kMaxBr = 6;  // brackets kept per lane for the lockstep refinement
+
+// Refine the bracket starting at sweep sample j and fold the root into the
+// running first-arrival choice (largest ray velocity; ties to the smaller
+// |theta_R - psi*|).
+__device__ __forceinline__ void refine_bracket(const SolveArgs& a, const Medium& m, int mode,
+                                               const double2* tab, int j, double psi_star,
+                                               bool el, bool* found, bool* ill, Entry* best) {
+  const double dth = kTwoPi / a.n_sweep;
+  double2 sa = tab[j];
+  double2 sb = tab[j + 1 == a.n_sweep ? 0 : j + 1];
+  double fa = wrap_pi(sa.y - psi_star);
+  double fb = wrap_pi(sb.y - psi_star);
+  double ta = (j + 0.5) * dth;
+  double tb = ta + dth;
+  double x, y;
+  bool ok = newton_root(m, mode, a.kernel, psi_star, ta, tb, sa.x, sb.x, fa, fb, &x, &y);
+  if (!ok) ok = bisect_root(m, mode, a.kernel, psi_star, ta, tb, fa, &x, &y);
+  if (!ok) return;
+  if (x >= kTwoPi) x -= kTwoPi;
+  if (x < 0.0) x += kTwoPi;
+  Vel v = energy_velocity(m, mode, a.kernel, x, y);
+  Entry cand;
+  ray_quantities(v, &cand);
+  cand.thR = x;
+  cand.thI = y;
+  double h = el ? 0.0 : homog_residual(v);
+  cand.res = fmax(fabs(h), fabs(wrap_pi(ray_angle(v) - psi_star)));
+  bool cand_ill = fabs((fb - fa) / (tb - ta)) < kIllSlope;
+  bool take;
+  if (!*found) take = true;
+  else if (cand.V > best->V * (1.0 + kTieRel)) take = true;
+  else take = fabs(cand.V - best->V) <= kTieRel * best->V &&
+              ang_dist(cand.thR, psi_star) < ang_dist(best->thR, psi_star);
+  if (take) {
+    *best = cand;
+    *ill = cand_ill;
+    *found = true;
+  }
+}
+
+__device__ __forceinline__ bool is_bracket(const double2* tab, int j, int n, double psi_star) {
+  double2 sa = tab[j];
+  double2 sb = tab[j + 1 == n ? 0 : j + 1];
+  if (isnan(sa.y) || isnan(sb.y)) return false;
+  double fa = wrap_pi(sa.y - psi_star);
+  double fb = wrap_pi(sb.y - psi_star);
+  if (fabs(fb - fa) >= kPi) return false;  // the +-pi seam, not a crossing
+  return brackets(fa, fb);
+}
+
 __global__ void __launch_bounds__(64) k_solve(SolveArgs a) {
   extern __shared__ double2 tab[];
+  __shared__ int s_br[64 * kMaxBr];
   const int half = a.n_dirs / 2;
   const int chunks = (half + 63) / 64;
   const int64_t job = blockIdx.x / chunks;
@@ -206,43 +258,29 @@ __global__ void __launch_bounds__(64) k_solve(SolveArgs a) {
   const Medium m = load_medium(c);
   const bool el = theta_i_zero(m, mode);
   const double psi_star = wrap_pi(d * (kTwoPi / a.n_dirs) - m.tilt);
-  const double dth = kTwoPi / a.n_sweep;
 
+  // phase 1: every sign change of the ray-direction miss over the sweep
+  int nbr = 0;
+  int* my = s_br + threadIdx.x * kMaxBr;
+  for (int j = 0; j < a.n_sweep; ++j) {
+    if (!is_bracket(tab, j, a.n_sweep, psi_star)) continue;
+    if (nbr < kMaxBr) my[nbr] = j;
+    ++nbr;
+  }
+  // phase 2: refine the kept brackets with all lanes in step
   bool found = false, ill = false;
   Entry best{};
-  for (int j = 0; j < a.n_sweep; ++j) {
-    double2 sa = tab[j];
-    double2 sb = tab[j + 1 == a.n_sweep ? 0 : j + 1];
-    if (isnan(sa.y) || isnan(sb.y)) continue;
-    double fa = wrap_pi(sa.y - psi_star);
-    double fb = wrap_pi(sb.y - psi_star);
-    if (fabs(fb - fa) >= kPi) continue;
-    if (!brackets(fa, fb)) continue;
-    double ta = (j + 0.5) * dth;
-    double tb = ta + dth;
-    double x, y;
-    if (!newton_root(m, mode, a.kernel, psi_star, ta, tb, sa.x, sb.x, fa, fb, &x, &y) &&
-        !bisect_root(m, mode, a.kernel, psi_star, ta, tb, fa, &x, &y))
-      continue;
-    if (x >= kTwoPi) x -= kTwoPi;
-    if (x < 0.0) x += kTwoPi;
-    Vel v = energy_velocity(m, mode, a.kernel, x, y);
-    Entry cand;
-    ray_quantities(v, &cand);
-    cand.thR = x;
-    cand.thI = y;
-    double h = el ? 0.0 : homog_residual(v);
-    cand.res = fmax(fabs(h), fabs(wrap_pi(ray_angle(v) - psi_star)));
-    bool cand_ill = fabs((fb - fa) / (tb - ta)) < kIllSlope;
-    bool take;
-    if (!found) take = true;
-    else if (cand.V > best.V * (1.0 + kTieRel)) take = true;
-    else take = fabs(cand.V - best.V) <= kTieRel * best.V &&
-                ang_dist(cand.thR, psi_star) < ang_dist(best.thR, psi_star);
-    if (take) {
-      best = cand;
-      ill = cand_ill;
-      found = true;
+  for (int sidx = 0; sidx < kMaxBr; ++sidx) {
+    if (__all(sidx >= nbr)) break;
+    if (sidx < nbr) refine_bracket(a, m, mode, tab, my[sidx], psi_star, el, &found, &ill, &best);
+  }
+  // rare: more brackets than slots; refine the rest in scan order
+  if (nbr > kMaxBr) {
+    int seen = 0;
+    for (int j = 0; j < a.n_sweep; ++j) {
+      if (!is_bracket(tab, j, a.n_sweep, psi_star)) continue;
+      if (seen++ < kMaxBr) continue;
+      refine_bracket(a, m, mode, tab, j, psi_star, el, &found, &ill, &best);
     }
   }
   if (!found) {

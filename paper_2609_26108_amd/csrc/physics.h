@@ -177,8 +177,8 @@ __device__ __forceinline__ bool brackets(double fa, double fb) {
 }
 
 // Illinois (modified regula falsi) on a bracket [a, b] of h(thR, .)
-__device__ __noinline__ double refine_thi(const Medium& m, int mode, int kernel, double thR,
-                                          double a, double b, double fa, double fb) {
+__device__ __forceinline__ double refine_thi(const Medium& m, int mode, int kernel, double thR,
+                                             double a, double b, double fa, double fb) {
   int side = 0;
   double c = 0.5 * (a + b);
   for (int it = 0; it < 80; ++it) {
@@ -187,7 +187,7 @@ __device__ __noinline__ double refine_thi(const Medium& m, int mode, int kernel,
     double fc = h_at(m, mode, kernel, thR, cn);
     double step = fabs(cn - c);
     c = cn;
-    if (fc == 0.0) return c;
+    if (fc == 0.0) break;
     if ((fc < 0.0) == (fa < 0.0)) {
       a = c;
       fa = fc;
@@ -206,35 +206,45 @@ __device__ __noinline__ double refine_thi(const Medium& m, int mode, int kernel,
 
 // theta_I(theta_R): root of the homogeneity residual nearest 0 in [-30, 30]
 // deg, found by an outward 0.25-degree scan.  Returns false if none.
-__device__ __noinline__ bool theta_imag(const Medium& m, int mode, int kernel, double thR,
-                                        double* thI) {
+// Written for wavefront lockstep: every lane first scans until the whole
+// wavefront has its bracket, then all lanes refine together.
+__device__ __forceinline__ bool theta_imag(const Medium& m, int mode, int kernel, double thR,
+                                           double* thI) {
   if (theta_i_zero(m, mode)) {
     *thI = 0.0;
     return true;
   }
   double h0 = h_at(m, mode, kernel, thR, 0.0);
+  bool done = (h0 == 0.0);
+  bool bp = false, bn = false;
+  double pa = 0.0, pb = 0.0, fpa = 0.0, fpb = 0.0;  // positive-side bracket
+  double na = 0.0, nb = 0.0, fna = 0.0, fnb = 0.0;  // negative-side bracket
+  double hp_lo = h0, hn_hi = h0;
+  for (int k = 0; k < kThiSteps; ++k) {
+    if (!done) {
+      double a = k * kThiStep, b = (k + 1) * kThiStep;
+      double hp_hi = h_at(m, mode, kernel, thR, b);
+      double hn_lo = h_at(m, mode, kernel, thR, -b);
+      bp = brackets(hp_lo, hp_hi);
+      bn = brackets(hn_lo, hn_hi);
+      if (bp) { pa = a; pb = b; fpa = hp_lo; fpb = hp_hi; }
+      if (bn) { na = -b; nb = -a; fna = hn_lo; fnb = hn_hi; }
+      done = bp || bn;
+      hp_lo = hp_hi;
+      hn_hi = hn_lo;
+    }
+    if (__all(done)) break;
+  }
   if (h0 == 0.0) {
     *thI = 0.0;
     return true;
   }
-  double hp_lo = h0, hn_hi = h0;
-  for (int k = 0; k < kThiSteps; ++k) {
-    double a = k * kThiStep, b = (k + 1) * kThiStep;
-    double hp_hi = h_at(m, mode, kernel, thR, b);
-    double hn_lo = h_at(m, mode, kernel, thR, -b);
-    bool bp = brackets(hp_lo, hp_hi);
-    bool bn = brackets(hn_lo, hn_hi);
-    if (bp || bn) {
-      double rp = bp ? refine_thi(m, mode, kernel, thR, a, b, hp_lo, hp_hi) : 0.0;
-      double rn = bn ? refine_thi(m, mode, kernel, thR, -b, -a, hn_lo, hn_hi) : 0.0;
-      if (bp && bn) *thI = (fabs(rn) < fabs(rp)) ? rn : rp;
-      else *thI = bp ? rp : rn;
-      return true;
-    }
-    hp_lo = hp_hi;
-    hn_hi = hn_lo;
-  }
-  return false;
+  if (!bp && !bn) return false;
+  double rp = bp ? refine_thi(m, mode, kernel, thR, pa, pb, fpa, fpb) : 0.0;
+  double rn = bn ? refine_thi(m, mode, kernel, thR, na, nb, fna, fnb) : 0.0;
+  if (bp && bn) *thI = (fabs(rn) < fabs(rp)) ? rn : rp;
+  else *thI = bp ? rp : rn;
+  return true;
 }
 
 struct Entry {

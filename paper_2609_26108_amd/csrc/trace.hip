@@ -1,23 +1,24 @@
-// First-arrival traveltime fields on a 2D forward-star graph (eqs 18-19,
+// First-arrival traveltime fields on 2D forward-star graphs (eqs 18-19,
 // 22-34; Algorithm 2, tracing) for gfx950.
 //
-// Each (source, field) pair is an independent min-plus problem: tau_R with
+// A call carries one or more jobs (grid + cache mode + sources).  Each
+// (job, source, field) triple is an independent min-plus problem: tau_R with
 // the propagation increments, tau_I with the attenuation increments (eqs 24,
-// 29-31).  The solver is a tiled, frontier-driven label-correcting
-// relaxation:
-//   - the grid is cut into TX x TZ tiles; a workgroup owns one (problem,
-//     tile), stages the tile plus an R-wide halo of tau and the class ids in
-//     LDS, and pulls every interior node over the star until the tile is
-//     locally converged (chaotic in-place updates are safe: every value ever
-//     written is the fold of some path, and values only decrease);
+// 29-31).  All problems advance together in the same launches:
+//   - every grid is cut into TX x TZ tiles; a workgroup owns one (problem,
+//     tile) per round, stages the tile plus an R-wide halo of the field and
+//     the class ids in LDS, pulls every interior node once over the star,
+//     then runs push iterations over a compacted frontier of improved nodes
+//     (LDS 64-bit atomic min) until the tile is locally converged;
 //   - changed nodes within R of a tile border activate the neighbouring
 //     tile for the next round (double-buffered flags, one counter per round);
 //   - rounds repeat until a round activates nothing.
-// The fixed point equals Dijkstra's result bitwise because both are the
-// minimum over paths of the left-to-right FP64 sum of the same weights.
+// Every value ever written is the left-to-right FP64 sum along some path and
+// values only decrease, so the fixed point is the minimum over paths --
+// bitwise what Dijkstra computes from the same weights, for any schedule.
 //
-// Predecessors (eq 33) are made schedule-independent: BFS hop counts over
-// the tight edges (tau_i + w_ij == tau_j) by the same tiled relaxation, then
+// Predecessors (eq 33) are schedule-independent: BFS hop counts over the
+// tight edges (tau_i + w_ij == tau_j) by the same tiled relaxation, then
 // pred_j = tight neighbour with the smallest (hop, offset index).  t* folds
 // the attenuation increments along the propagation predecessor tree.
 #include <hip/hip_runtime.h>
@@ -33,44 +34,44 @@
 
 namespace chert {
 
-constexpr int kRelaxThreads = 256;
-constexpr int kMaxNodesPerThread = 4;
-constexpr int kLocalIterCap = 512;
+constexpr int kRelaxThreads = 1024;  // one node per thread: tiles <= 1024 nodes
+constexpr int kLocalIterCap = 4096;
 constexpr int32_t kHopUnset = 0x7fffffff;
 constexpr int kFieldR = 0, kFieldI = 1;
+constexpr size_t kWLdsBytes = 48 * 1024;  // class-pair table staged in LDS up to this
+
+struct JobDev {
+  int nx, nz;     // nodes (nx * nz < 2^31)
+  int ntx, ntz;   // tiles per axis
+  int K;          // classes of the job's cache
+  int w_in_lds;   // stage W in LDS
+  const int32_t* class_id;
+  const double* W;  // [2][K][K][n_off]: propagation then attenuation weights
+};
 
 struct ProbDev {
-  double* tau;     // [n_nodes] this problem's traveltime field
+  double* tau;     // [n_nodes] this problem's field
   int32_t* hop;    // [n_nodes] hop counts, then predecessor offset index
   int32_t* pred;   // [n_nodes] or nullptr
   double* tstar;   // [n_nodes] or nullptr (propagation problems only)
   int64_t src;
-  int32_t field;   // 0 = propagation (w_R), 1 = attenuation (w_I)
-  int32_t tstar_of; // for t*: index of the propagation problem, else -1
-};
-
-struct Geom {
-  int64_t nx, nz;
-  int tx, tz;      // tile size
-  int ntx, ntz;    // tiles per axis
-  int R;
-  int n_off;
-  int lw, lh;      // LDS tile + halo extent
-  int K;           // classes
+  int job;
+  int field;       // 0 = propagation (w_R), 1 = attenuation (w_I)
+  int tile_base;   // first global tile index of this problem
+  int pad;
 };
 
 struct RelaxArgs {
-  Geom g;
-  const int32_t* class_id;
+  int tx, tz, R, n_off, lw, lh;
+  int n_prob, n_tiles;  // problems, tiles over all problems
+  const JobDev* jobs;
+  const ProbDev* probs;
   const int32_t* ox;
   const int32_t* oz;
-  const double* W;  // [2][K][K][n_off]
-  ProbDev* probs;
-  int n_prob;
-  int32_t* flags;   // [2][n_prob][n_tiles]
-  int32_t* counter; // [max_rounds + 2]
-  int32_t* err;     // [1] out-of-range class ids seen
-  int w_in_lds;
+  int32_t* flags;    // [2][n_tiles]
+  int32_t* counter;  // [max_rounds + 2]
+  int32_t* err;      // out-of-range class ids seen
+  int w_lds_doubles; // LDS room for W
 };
 
 // ------------------------------------------------------------- weights ---
@@ -105,37 +106,35 @@ __global__ void k_weights(double* W, int K, int n_off, const double* V, const do
 
 // ---------------------------------------------------------------- init ---
 
-__global__ void k_init_fields(ProbDev* probs, int n_prob, int64_t n_nodes, int32_t* err) {
-  int64_t total = (int64_t)n_prob * n_nodes;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    int p = (int)(t / n_nodes);
-    int64_t j = t % n_nodes;
-    ProbDev pr = probs[p];
-    if (t == 0) *err = 0;
+// blockIdx.y = problem; x strides over its nodes
+__global__ void k_init_fields(const ProbDev* probs, const JobDev* jobs, int32_t* err) {
+  const ProbDev pr = probs[blockIdx.y];
+  const int64_t n = (int64_t)jobs[pr.job].nx * jobs[pr.job].nz;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *err = 0;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
     pr.tau[j] = (j == pr.src) ? 0.0 : INFINITY;
     pr.hop[j] = (j == pr.src) ? 0 : kHopUnset;
     if (pr.tstar) pr.tstar[j] = (j == pr.src) ? 0.0 : NAN;
   }
 }
 
-// Clear flags and counters, then activate each problem's source tile.
-__global__ void k_init_flags(int32_t* flags, int64_t n_flags, int32_t* counter,
-                             int n_counter) {
+__global__ void k_clear_flags(int32_t* flags, int64_t n_flags, int32_t* counter, int n_counter) {
   int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t t = tid; t < n_flags; t += (int64_t)gridDim.x * blockDim.x) flags[t] = 0;
   for (int64_t t = tid; t < n_counter; t += (int64_t)gridDim.x * blockDim.x) counter[t] = 0;
 }
 
-__global__ void k_seed_flags(int32_t* flags, int32_t* counter, const ProbDev* probs, int n_prob,
-                             Geom g, int phase_tstar) {
+// activate the source tile of every problem (t* phase: only problems with t*)
+__global__ void k_seed_flags(int32_t* flags, int32_t* counter, const ProbDev* probs,
+                             const JobDev* jobs, int n_prob, int tx, int tz, int tstar_phase) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_prob) return;
-  if (phase_tstar && probs[p].tstar == nullptr) return;
-  int64_t s = probs[p].src;
-  int tx = (int)((s % g.nx) / g.tx), tz = (int)((s / g.nx) / g.tz);
-  int n_tiles = g.ntx * g.ntz;
-  flags[(int64_t)p * n_tiles + tz * g.ntx + tx] = 1;
+  const ProbDev pr = probs[p];
+  if (tstar_phase && pr.tstar == nullptr) return;
+  const JobDev jb = jobs[pr.job];
+  int sx = (int)(pr.src % jb.nx), sz = (int)(pr.src / jb.nx);
+  flags[pr.tile_base + (sz / tz) * jb.ntx + (sx / tx)] = 1;
   atomicAdd(&counter[0], 1);
 }
 
@@ -143,30 +142,46 @@ __global__ void k_seed_flags(int32_t* flags, int32_t* counter, const ProbDev* pr
 
 struct TileCtx {
   int p, t, tx, tz;
-  int64_t x0, z0;  // first interior node
-  int txe, tze;    // interior extent (ragged at the grid edge)
+  int x0, z0;    // first interior node
+  int txe, tze;  // interior extent (ragged at the grid edge)
+  int active;
 };
 
-__device__ __forceinline__ bool tile_begin(const RelaxArgs& a, int round, TileCtx* c,
-                                           int* s_flag) {
-  const int n_tiles = a.g.ntx * a.g.ntz;
-  c->p = blockIdx.x / n_tiles;
-  c->t = blockIdx.x % n_tiles;
-  int32_t* fin = a.flags + (int64_t)(round & 1) * a.n_prob * n_tiles;
+// Claim this workgroup's (problem, tile) for the round: find the problem by
+// binary search over the tile bases, read and clear the tile's flag.
+__device__ __forceinline__ TileCtx tile_begin(const RelaxArgs& a, int round, int* s_flag,
+                                              int* s_prob) {
+  const int T = blockIdx.x;
+  int32_t* fin = a.flags + (int64_t)(round & 1) * a.n_tiles;
   if (threadIdx.x == 0) {
-    int32_t f = fin[(int64_t)c->p * n_tiles + c->t];
+    int32_t f = fin[T];
     *s_flag = f;
-    if (f) fin[(int64_t)c->p * n_tiles + c->t] = 0;
+    if (f) {
+      fin[T] = 0;
+      int lo = 0, hi = a.n_prob - 1;
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (a.probs[mid].tile_base <= T) lo = mid;
+        else hi = mid - 1;
+      }
+      *s_prob = lo;
+    }
   }
   __syncthreads();
-  if (!*s_flag) return false;
-  c->tx = c->t % a.g.ntx;
-  c->tz = c->t / a.g.ntx;
-  c->x0 = (int64_t)c->tx * a.g.tx;
-  c->z0 = (int64_t)c->tz * a.g.tz;
-  c->txe = (int)min((int64_t)a.g.tx, a.g.nx - c->x0);
-  c->tze = (int)min((int64_t)a.g.tz, a.g.nz - c->z0);
-  return true;
+  TileCtx c;
+  c.active = *s_flag;
+  if (!c.active) return c;
+  c.p = *s_prob;
+  const ProbDev& pr = a.probs[c.p];
+  const JobDev& jb = a.jobs[pr.job];
+  c.t = T - pr.tile_base;
+  c.tx = c.t % jb.ntx;
+  c.tz = c.t / jb.ntx;
+  c.x0 = c.tx * a.tx;
+  c.z0 = c.tz * a.tz;
+  c.txe = min(a.tx, jb.nx - c.x0);
+  c.tze = min(a.tz, jb.nz - c.z0);
+  return c;
 }
 
 // which neighbour tiles see node (x, z) of this tile in their halo
@@ -185,265 +200,388 @@ __device__ __forceinline__ int border_bits(int x, int z, int tx, int tz, int R) 
 }
 
 __device__ __forceinline__ void activate(const RelaxArgs& a, int round, const TileCtx& c,
-                                         int mask) {
-  const int n_tiles = a.g.ntx * a.g.ntz;
-  int32_t* fout = a.flags + (int64_t)((round + 1) & 1) * a.n_prob * n_tiles;
+                                         const ProbDev& pr, const JobDev& jb, int mask) {
+  int32_t* fout = a.flags + (int64_t)((round + 1) & 1) * a.n_tiles;
   for (int bit = 0; bit < 9; ++bit) {
     if (!(mask & (1 << bit))) continue;
     int dx = bit % 3 - 1, dz = bit / 3 - 1;
     int nx_ = c.tx + dx, nz_ = c.tz + dz;
-    if (nx_ < 0 || nx_ >= a.g.ntx || nz_ < 0 || nz_ >= a.g.ntz) continue;
-    int32_t* f = &fout[(int64_t)c.p * n_tiles + nz_ * a.g.ntx + nx_];
+    if (nx_ < 0 || nx_ >= jb.ntx || nz_ < 0 || nz_ >= jb.ntz) continue;
+    int32_t* f = &fout[pr.tile_base + nz_ * jb.ntx + nx_];
     if (atomicOr(f, 1) == 0) atomicAdd(&a.counter[round + 1], 1);
   }
 }
 
-// Stage class ids of tile + halo; out-of-grid = -1, out-of-range ids = -2.
-__device__ __forceinline__ void load_classes(const RelaxArgs& a, const TileCtx& c,
-                                             int32_t* cls_l) {
-  const int R = a.g.R, lw = a.g.lw, n = lw * a.g.lh;
-  for (int q = threadIdx.x; q < n; q += blockDim.x) {
-    int64_t gx = c.x0 + (q % lw) - R, gz = c.z0 + (q / lw) - R;
-    int32_t k = -1;
-    if (gx >= 0 && gx < a.g.nx && gz >= 0 && gz < a.g.nz) {
-      k = a.class_id[gx + a.g.nx * gz];
-      if (k < 0 || k >= a.g.K) {
-        atomicAdd(a.err, 1);
-        k = -2;
-      }
-    }
-    cls_l[q] = k;
-  }
-}
-
-__device__ __forceinline__ void load_offsets(const RelaxArgs& a, int32_t* off_l) {
-  for (int o = threadIdx.x; o < a.g.n_off; o += blockDim.x)
-    off_l[o] = a.ox[o] + a.oz[o] * a.g.lw;
-}
-
 struct Smem {
-  double* val;     // [lw*lh]
-  int32_t* ival;   // [lw*lh]
-  int32_t* cls;    // [lw*lh]
-  int32_t* off;    // [n_off]
-  double* W;       // [K*K*n_off] when staged
+  double* val;    // [lw*lh] field values
+  int32_t* ival;  // [lw*lh] hop counts / predecessor offsets
+  int32_t* cls;   // [lw*lh] class ids: -1 outside the grid, -2 out of range
+  int32_t* off;   // [n_off] LDS offsets of the star
+  double* W;      // staged class-pair table
+  int32_t* l0;    // frontier buffers (interior LDS indices)
+  int32_t* l1;
+  int32_t* inq;   // [lw*lh] 1 while queued
 };
 
 __device__ __forceinline__ Smem carve(const RelaxArgs& a, void* base) {
   Smem s;
-  const int n = a.g.lw * a.g.lh;
+  const int n = a.lw * a.lh;
   char* p = (char*)base;
   s.val = (double*)p;
   p += sizeof(double) * n;
+  s.W = (double*)p;
+  p += sizeof(double) * a.w_lds_doubles;
   s.ival = (int32_t*)p;
   p += sizeof(int32_t) * n;
   s.cls = (int32_t*)p;
   p += sizeof(int32_t) * n;
+  s.inq = (int32_t*)p;
+  p += sizeof(int32_t) * n;
   s.off = (int32_t*)p;
-  p += sizeof(int32_t) * ((a.g.n_off + 1) & ~1);
-  s.W = (double*)p;
+  p += sizeof(int32_t) * ((a.n_off + 1) & ~1);
+  s.l0 = (int32_t*)p;
+  p += sizeof(int32_t) * a.tx * a.tz;
+  s.l1 = (int32_t*)p;
   return s;
+}
+
+static size_t lds_bytes(int lw, int lh, int w_doubles, int n_off, int tx, int tz) {
+  const size_t n = (size_t)lw * lh;
+  return sizeof(double) * (n + w_doubles) + sizeof(int32_t) * 3 * n +
+         sizeof(int32_t) * ((n_off + 1) & ~1) + sizeof(int32_t) * 2 * tx * tz;
+}
+
+// Stage class ids and star offsets of tile + halo.
+__device__ __forceinline__ void load_common(const RelaxArgs& a, const TileCtx& c, const JobDev& jb,
+                                            const Smem& s) {
+  const int R = a.R, lw = a.lw, n = lw * a.lh;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    int gx = c.x0 + (q % lw) - R, gz = c.z0 + (q / lw) - R;
+    int32_t k = -1;
+    if (gx >= 0 && gx < jb.nx && gz >= 0 && gz < jb.nz) {
+      k = jb.class_id[(int64_t)gx + (int64_t)jb.nx * gz];
+      if (k < 0 || k >= jb.K) {
+        atomicAdd(a.err, 1);
+        k = -2;
+      }
+    }
+    s.cls[q] = k;
+    s.inq[q] = 0;
+  }
+  for (int o = threadIdx.x; o < a.n_off; o += blockDim.x) s.off[o] = a.ox[o] + a.oz[o] * lw;
+}
+
+__device__ __forceinline__ const double* stage_w(const RelaxArgs& a, const JobDev& jb, int field,
+                                                 const Smem& s) {
+  const int kk = jb.K * jb.K * a.n_off;
+  const double* Wf = jb.W + (int64_t)field * kk;
+  if (!jb.w_in_lds) return Wf;
+  for (int q = threadIdx.x; q < kk; q += blockDim.x) s.W[q] = Wf[q];
+  return s.W;
+}
+
+// Wavefront-aggregated append: one LDS atomic per wavefront (ballot +
+// popcount), lane slots from the mask of lower lanes.
+__device__ __forceinline__ void frontier_add(bool flag, int node, int32_t* list, int* count) {
+  unsigned long long b = __ballot(flag);
+  if (b == 0ull) return;
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)b) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(count, __popcll(b));
+  base = __shfl(base, leader);
+  if (flag) list[base + __popcll(b & ((1ull << lane) - 1ull))] = node;
+}
+
+__device__ __forceinline__ bool interior(int l, int lw, int R, int txe, int tze) {
+  int x = l % lw - R, z = l / lw - R;
+  return x >= 0 && x < txe && z >= 0 && z < tze;
+}
+
+__device__ __forceinline__ unsigned long long dbits(double x) {
+  return (unsigned long long)__double_as_longlong(x);
+}
+
+// LDS index of this thread's interior node, or -1.
+__device__ __forceinline__ int my_node(const RelaxArgs& a, const TileCtx& c) {
+  const int q = threadIdx.x;
+  if (q >= a.tx * a.tz) return -1;
+  const int x = q % a.tx, z = q / a.tx;
+  if (x >= c.txe || z >= c.tze) return -1;
+  return (z + a.R) * a.lw + (x + a.R);
+}
+
+// Loop bound shared by every thread (a multiple of the block size), so each
+// wavefront reaches every frontier_add together.
+__device__ __forceinline__ int uniform_bound(int total) {
+  return (total + kRelaxThreads - 1) / kRelaxThreads * kRelaxThreads;
 }
 
 // ----------------------------------------------------- relaxation phases ---
 
-// Phase TAU: tau_j <- min(tau_j, tau_i + w_ij) over the star (eq 31, pull).
+// Phase TAU: tau_j <- min(tau_j, tau_i + w_ij) (eq 31).
 __global__ void __launch_bounds__(kRelaxThreads) k_relax_tau(RelaxArgs a, int round) {
   extern __shared__ double smem_d[];
-  __shared__ int s_flag, s_mask;
-  TileCtx c;
-  if (!tile_begin(a, round, &c, &s_flag)) return;
-  Smem s = carve(a, smem_d);
-  const int R = a.g.R, lw = a.g.lw, n = lw * a.g.lh, K = a.g.K, n_off = a.g.n_off;
+  __shared__ int s_flag, s_prob, s_mask, s_cnt[2];
+  const TileCtx c = tile_begin(a, round, &s_flag, &s_prob);
+  if (!c.active) return;
+  const Smem s = carve(a, smem_d);
+  const int R = a.R, lw = a.lw, n = lw * a.lh, n_off = a.n_off;
   const ProbDev pr = a.probs[c.p];
-  const double* Wf = a.W + (int64_t)pr.field * K * K * n_off;
-  if (threadIdx.x == 0) s_mask = 0;
-  load_classes(a, c, s.cls);
-  load_offsets(a, s.off);
+  const JobDev jb = a.jobs[pr.job];
+  const int K = jb.K;
+  if (threadIdx.x == 0) {
+    s_mask = 0;
+    s_cnt[0] = 0;
+    s_cnt[1] = 0;
+  }
+  load_common(a, c, jb, s);
   for (int q = threadIdx.x; q < n; q += blockDim.x) {
-    int64_t gx = c.x0 + (q % lw) - R, gz = c.z0 + (q / lw) - R;
-    bool in = gx >= 0 && gx < a.g.nx && gz >= 0 && gz < a.g.nz;
-    s.val[q] = in ? pr.tau[gx + a.g.nx * gz] : INFINITY;
+    int gx = c.x0 + (q % lw) - R, gz = c.z0 + (q / lw) - R;
+    bool in = gx >= 0 && gx < jb.nx && gz >= 0 && gz < jb.nz;
+    s.val[q] = in ? pr.tau[(int64_t)gx + (int64_t)jb.nx * gz] : INFINITY;
   }
-  if (a.w_in_lds)
-    for (int q = threadIdx.x; q < K * K * n_off; q += blockDim.x) s.W[q] = Wf[q];
+  const double* Wp = stage_w(a, jb, pr.field, s);
   __syncthreads();
-  const double* Wp = a.w_in_lds ? s.W : Wf;
+  const int ml = my_node(a, c);
+  const double orig = ml >= 0 ? s.val[ml] : 0.0;
 
-  int li[kMaxNodesPerThread];
-  double orig[kMaxNodesPerThread];
-  int mine = 0;
-  for (int q = threadIdx.x; q < a.g.tx * a.g.tz && mine < kMaxNodesPerThread; q += blockDim.x) {
-    int x = q % a.g.tx, z = q / a.g.tx;
-    if (x >= c.txe || z >= c.tze) continue;
-    li[mine] = (z + R) * lw + (x + R);
-    orig[mine] = s.val[li[mine]];
-    ++mine;
+  // pull once over every interior node
+  {
+    bool improved = false;
+    if (ml >= 0) {
+      const int kj = s.cls[ml];
+      if (kj >= 0) {
+        const double cur = s.val[ml];
+        double best = cur;
+        for (int o = 0; o < n_off; ++o) {
+          const int ii = ml - s.off[o];
+          const int ki = s.cls[ii];
+          if (ki < 0) continue;
+          const double cand = __dadd_rn(s.val[ii], Wp[(ki * K + kj) * n_off + o]);
+          if (cand < best) best = cand;
+        }
+        if (best < cur) {
+          s.val[ml] = best;
+          improved = true;
+          s.inq[ml] = 1;
+        }
+      }
+    }
+    frontier_add(improved, ml, s.l0, &s_cnt[0]);
   }
-  int it = 0, changed;
-  do {
-    changed = 0;
-    for (int m = 0; m < mine; ++m) {
-      const int l = li[m];
-      const int kj = s.cls[l];
-      if (kj < 0) continue;
-      const double cur = s.val[l];
-      double best = cur;
-      for (int o = 0; o < n_off; ++o) {
-        const int ii = l - s.off[o];
-        const int ki = s.cls[ii];
-        if (ki < 0) continue;
-        const double cand = __dadd_rn(s.val[ii], Wp[((int64_t)ki * K + kj) * n_off + o]);
-        if (cand < best) best = cand;
-      }
-      if (best < cur) {
-        s.val[l] = best;
-        changed = 1;
-      }
-    }
-    ++it;
-  } while (__syncthreads_or(changed) && it < kLocalIterCap);
+  __syncthreads();
 
-  int mask = (it >= kLocalIterCap) ? (1 << 4) : 0;  // bit 4 = this tile again
-  for (int m = 0; m < mine; ++m) {
-    const int l = li[m];
-    if (s.val[l] < orig[m]) {
-      int x = l % lw - R, z = l / lw - R;
-      pr.tau[(c.x0 + x) + a.g.nx * (c.z0 + z)] = s.val[l];
-      mask |= border_bits(x, z, a.g.tx, a.g.tz, R);
+  // push iterations over the frontier
+  const int q_step = kRelaxThreads / n_off, r_step = kRelaxThreads % n_off;
+  int cur = 0, it = 0;
+  int nf = s_cnt[0];
+  while (nf > 0 && it < kLocalIterCap) {
+    const int nxt = cur ^ 1;
+    int32_t* const lcur = cur ? s.l1 : s.l0;
+    int32_t* const lnxt = cur ? s.l0 : s.l1;
+    for (int f = threadIdx.x; f < nf; f += blockDim.x) s.inq[lcur[f]] = 0;
+    if (threadIdx.x == 0) s_cnt[nxt] = 0;
+    __syncthreads();
+    const int total = nf * n_off;
+    const int bound = uniform_bound(total);
+    int f = threadIdx.x / n_off, o = threadIdx.x % n_off;
+    for (int item = threadIdx.x; item < bound; item += kRelaxThreads) {
+      bool improved = false;
+      int j = 0;
+      if (item < total) {
+        const int i = lcur[f];
+        j = i + s.off[o];
+        const int ki = s.cls[i], kj = s.cls[j];
+        if (kj >= 0 && interior(j, lw, R, c.txe, c.tze)) {
+          const double cand = __dadd_rn(s.val[i], Wp[(ki * K + kj) * n_off + o]);
+          const unsigned long long old =
+              atomicMin((unsigned long long*)&s.val[j], dbits(cand));
+          if (dbits(cand) < old) improved = atomicExch(&s.inq[j], 1) == 0;
+        }
+      }
+      frontier_add(improved, j, lnxt, &s_cnt[nxt]);
+      f += q_step;
+      o += r_step;
+      if (o >= n_off) {
+        o -= n_off;
+        ++f;
+      }
     }
+    __syncthreads();
+    nf = s_cnt[nxt];
+    cur = nxt;
+    ++it;
+    __syncthreads();
+  }
+
+  int mask = (nf > 0) ? (1 << 4) : 0;  // bit 4 = this tile again
+  if (ml >= 0 && s.val[ml] < orig) {
+    int x = ml % lw - R, z = ml / lw - R;
+    pr.tau[(int64_t)(c.x0 + x) + (int64_t)jb.nx * (c.z0 + z)] = s.val[ml];
+    mask |= border_bits(x, z, a.tx, a.tz, R);
   }
   if (mask) atomicOr(&s_mask, mask);
   __syncthreads();
-  if (threadIdx.x == 0 && s_mask) activate(a, round, c, s_mask);
+  if (threadIdx.x == 0 && s_mask) activate(a, round, c, pr, jb, s_mask);
 }
 
 // Phase HOP: BFS hop counts over tight edges, h_j <- min(h_j, h_i + 1).
 __global__ void __launch_bounds__(kRelaxThreads) k_relax_hop(RelaxArgs a, int round) {
   extern __shared__ double smem_d[];
-  __shared__ int s_flag, s_mask;
-  TileCtx c;
-  if (!tile_begin(a, round, &c, &s_flag)) return;
-  Smem s = carve(a, smem_d);
-  const int R = a.g.R, lw = a.g.lw, n = lw * a.g.lh, K = a.g.K, n_off = a.g.n_off;
+  __shared__ int s_flag, s_prob, s_mask, s_cnt[2];
+  const TileCtx c = tile_begin(a, round, &s_flag, &s_prob);
+  if (!c.active) return;
+  const Smem s = carve(a, smem_d);
+  const int R = a.R, lw = a.lw, n = lw * a.lh, n_off = a.n_off;
   const ProbDev pr = a.probs[c.p];
-  const double* Wf = a.W + (int64_t)pr.field * K * K * n_off;
-  if (threadIdx.x == 0) s_mask = 0;
-  load_classes(a, c, s.cls);
-  load_offsets(a, s.off);
+  const JobDev jb = a.jobs[pr.job];
+  const int K = jb.K;
+  if (threadIdx.x == 0) {
+    s_mask = 0;
+    s_cnt[0] = 0;
+    s_cnt[1] = 0;
+  }
+  load_common(a, c, jb, s);
   for (int q = threadIdx.x; q < n; q += blockDim.x) {
-    int64_t gx = c.x0 + (q % lw) - R, gz = c.z0 + (q / lw) - R;
-    bool in = gx >= 0 && gx < a.g.nx && gz >= 0 && gz < a.g.nz;
-    int64_t g = gx + a.g.nx * gz;
+    int gx = c.x0 + (q % lw) - R, gz = c.z0 + (q / lw) - R;
+    bool in = gx >= 0 && gx < jb.nx && gz >= 0 && gz < jb.nz;
+    int64_t g = (int64_t)gx + (int64_t)jb.nx * gz;
     s.val[q] = in ? pr.tau[g] : INFINITY;
     s.ival[q] = in ? pr.hop[g] : kHopUnset;
   }
-  if (a.w_in_lds)
-    for (int q = threadIdx.x; q < K * K * n_off; q += blockDim.x) s.W[q] = Wf[q];
+  const double* Wp = stage_w(a, jb, pr.field, s);
   __syncthreads();
-  const double* Wp = a.w_in_lds ? s.W : Wf;
+  const int ml = my_node(a, c);
+  const int32_t orig = ml >= 0 ? s.ival[ml] : 0;
 
-  int li[kMaxNodesPerThread];
-  int32_t orig[kMaxNodesPerThread];
-  int mine = 0;
-  for (int q = threadIdx.x; q < a.g.tx * a.g.tz && mine < kMaxNodesPerThread; q += blockDim.x) {
-    int x = q % a.g.tx, z = q / a.g.tx;
-    if (x >= c.txe || z >= c.tze) continue;
-    li[mine] = (z + R) * lw + (x + R);
-    orig[mine] = s.ival[li[mine]];
-    ++mine;
+  {
+    bool improved = false;
+    if (ml >= 0) {
+      const int kj = s.cls[ml];
+      const double tj = s.val[ml];
+      if (kj >= 0 && tj < INFINITY) {
+        const int32_t cur = s.ival[ml];
+        int32_t best = cur;
+        for (int o = 0; o < n_off; ++o) {
+          const int ii = ml - s.off[o];
+          const int ki = s.cls[ii];
+          const int32_t hi = s.ival[ii];
+          if (ki < 0 || hi == kHopUnset || hi + 1 >= best) continue;
+          if (__dadd_rn(s.val[ii], Wp[(ki * K + kj) * n_off + o]) == tj) best = hi + 1;
+        }
+        if (best < cur) {
+          s.ival[ml] = best;
+          improved = true;
+          s.inq[ml] = 1;
+        }
+      }
+    }
+    frontier_add(improved, ml, s.l0, &s_cnt[0]);
   }
-  int it = 0, changed;
-  do {
-    changed = 0;
-    for (int m = 0; m < mine; ++m) {
-      const int l = li[m];
-      const int kj = s.cls[l];
-      const double tj = s.val[l];
-      if (kj < 0 || !(tj < INFINITY)) continue;
-      const int32_t cur = s.ival[l];
-      int32_t best = cur;
-      for (int o = 0; o < n_off; ++o) {
-        const int ii = l - s.off[o];
-        const int ki = s.cls[ii];
-        const int32_t hi = s.ival[ii];
-        if (ki < 0 || hi == kHopUnset || hi + 1 >= best) continue;
-        if (__dadd_rn(s.val[ii], Wp[((int64_t)ki * K + kj) * n_off + o]) == tj) best = hi + 1;
-      }
-      if (best < cur) {
-        s.ival[l] = best;
-        changed = 1;
-      }
-    }
-    ++it;
-  } while (__syncthreads_or(changed) && it < kLocalIterCap);
+  __syncthreads();
 
-  int mask = (it >= kLocalIterCap) ? (1 << 4) : 0;
-  for (int m = 0; m < mine; ++m) {
-    const int l = li[m];
-    if (s.ival[l] < orig[m]) {
-      int x = l % lw - R, z = l / lw - R;
-      pr.hop[(c.x0 + x) + a.g.nx * (c.z0 + z)] = s.ival[l];
-      mask |= border_bits(x, z, a.g.tx, a.g.tz, R);
+  const int q_step = kRelaxThreads / n_off, r_step = kRelaxThreads % n_off;
+  int cur = 0, it = 0;
+  int nf = s_cnt[0];
+  while (nf > 0 && it < kLocalIterCap) {
+    const int nxt = cur ^ 1;
+    int32_t* const lcur = cur ? s.l1 : s.l0;
+    int32_t* const lnxt = cur ? s.l0 : s.l1;
+    for (int f = threadIdx.x; f < nf; f += blockDim.x) s.inq[lcur[f]] = 0;
+    if (threadIdx.x == 0) s_cnt[nxt] = 0;
+    __syncthreads();
+    const int total = nf * n_off;
+    const int bound = uniform_bound(total);
+    int f = threadIdx.x / n_off, o = threadIdx.x % n_off;
+    for (int item = threadIdx.x; item < bound; item += kRelaxThreads) {
+      bool improved = false;
+      int j = 0;
+      if (item < total) {
+        const int i = lcur[f];
+        j = i + s.off[o];
+        const int ki = s.cls[i], kj = s.cls[j];
+        if (kj >= 0 && interior(j, lw, R, c.txe, c.tze)) {
+          const int32_t cand = s.ival[i] + 1;
+          if (cand < s.ival[j] &&
+              __dadd_rn(s.val[i], Wp[(ki * K + kj) * n_off + o]) == s.val[j]) {
+            const int32_t old = atomicMin(&s.ival[j], cand);
+            if (cand < old) improved = atomicExch(&s.inq[j], 1) == 0;
+          }
+        }
+      }
+      frontier_add(improved, j, lnxt, &s_cnt[nxt]);
+      f += q_step;
+      o += r_step;
+      if (o >= n_off) {
+        o -= n_off;
+        ++f;
+      }
     }
+    __syncthreads();
+    nf = s_cnt[nxt];
+    cur = nxt;
+    ++it;
+    __syncthreads();
+  }
+
+  int mask = (nf > 0) ? (1 << 4) : 0;
+  if (ml >= 0 && s.ival[ml] < orig) {
+    int x = ml % lw - R, z = ml / lw - R;
+    pr.hop[(int64_t)(c.x0 + x) + (int64_t)jb.nx * (c.z0 + z)] = s.ival[ml];
+    mask |= border_bits(x, z, a.tx, a.tz, R);
   }
   if (mask) atomicOr(&s_mask, mask);
   __syncthreads();
-  if (threadIdx.x == 0 && s_mask) activate(a, round, c, s_mask);
+  if (threadIdx.x == 0 && s_mask) activate(a, round, c, pr, jb, s_mask);
 }
 
 // pred_j = tight in-neighbour with hop_j - 1 and the smallest offset index.
-// Afterwards hop[] holds the predecessor's offset index (or -1) for t*.
+// blockIdx.y = problem.
 __global__ void k_pred(RelaxArgs a) {
-  const int64_t n_nodes = a.g.nx * a.g.nz;
-  const int K = a.g.K, n_off = a.g.n_off;
-  int64_t total = (int64_t)a.n_prob * n_nodes;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int p = (int)(t / n_nodes);
-    const int64_t j = t % n_nodes;
-    const ProbDev pr = a.probs[p];
-    const double* Wf = a.W + (int64_t)pr.field * K * K * n_off;
+  const ProbDev pr = a.probs[blockIdx.y];
+  const JobDev jb = a.jobs[pr.job];
+  const int K = jb.K, n_off = a.n_off;
+  const int64_t n_nodes = (int64_t)jb.nx * jb.nz;
+  const double* Wf = jb.W + (int64_t)pr.field * K * K * n_off;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_nodes;
+       j += (int64_t)gridDim.x * blockDim.x) {
     const int32_t hj = pr.hop[j];
-    int32_t best = -1, best_o = -1;
-    const int64_t jx = j % a.g.nx, jz = j / a.g.nx;
-    const int32_t kj = a.class_id[j];
+    int32_t best = -1;
+    const int jx = (int)(j % jb.nx), jz = (int)(j / jb.nx);
+    const int32_t kj = jb.class_id[j];
     if (j != pr.src && hj != kHopUnset && kj >= 0 && kj < K) {
       const double tj = pr.tau[j];
       for (int o = 0; o < n_off; ++o) {
-        int64_t ix = jx - a.ox[o], iz = jz - a.oz[o];
-        if (ix < 0 || ix >= a.g.nx || iz < 0 || iz >= a.g.nz) continue;
-        int64_t i = ix + a.g.nx * iz;
+        int ix = jx - a.ox[o], iz = jz - a.oz[o];
+        if (ix < 0 || ix >= jb.nx || iz < 0 || iz >= jb.nz) continue;
+        int64_t i = (int64_t)ix + (int64_t)jb.nx * iz;
         if (pr.hop[i] != hj - 1) continue;
-        int32_t ki = a.class_id[i];
+        int32_t ki = jb.class_id[i];
         if (ki < 0 || ki >= K) continue;
-        if (__dadd_rn(pr.tau[i], Wf[((int64_t)ki * K + kj) * n_off + o]) == tj) {
+        if (__dadd_rn(pr.tau[i], Wf[(ki * K + kj) * n_off + o]) == tj) {
           best = (int32_t)i;
-          best_o = o;
           break;
         }
       }
     }
-    (void)best_o;
     if (pr.pred) pr.pred[j] = best;
   }
 }
 
-// pred offsets must be written only after every hop read: separate pass
+// Separate pass (after every hop read): hop[] := predecessor offset index.
 __global__ void k_pred_offsets(RelaxArgs a) {
-  const int64_t n_nodes = a.g.nx * a.g.nz;
-  int64_t total = (int64_t)a.n_prob * n_nodes;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int p = (int)(t / n_nodes);
-    const int64_t j = t % n_nodes;
-    const ProbDev pr = a.probs[p];
-    if (!pr.pred) continue;
+  const ProbDev pr = a.probs[blockIdx.y];
+  if (!pr.pred) return;
+  const JobDev jb = a.jobs[pr.job];
+  const int64_t n_nodes = (int64_t)jb.nx * jb.nz;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_nodes;
+       j += (int64_t)gridDim.x * blockDim.x) {
     int32_t i = pr.pred[j];
     int32_t o_idx = -1;
     if (i >= 0) {
-      int dx = (int)(j % a.g.nx - i % a.g.nx), dz = (int)(j / a.g.nx - i / a.g.nx);
-      for (int o = 0; o < a.g.n_off; ++o)
+      int dx = (int)(j % jb.nx) - (int)(i % jb.nx), dz = (int)(j / jb.nx) - (int)(i / jb.nx);
+      for (int o = 0; o < a.n_off; ++o)
         if (a.ox[o] == dx && a.oz[o] == dz) {
           o_idx = o;
           break;
@@ -453,150 +591,185 @@ __global__ void k_pred_offsets(RelaxArgs a) {
   }
 }
 
-// Phase TSTAR: t*_j = t*_pred + w_I(pred -> j) once t*_pred is known.
+// Phase TSTAR: t*_j = t*_pred + w_I(pred -> j) once t*_pred is known; a
+// node whose value became known pushes to the children naming it as their
+// predecessor.
 __global__ void __launch_bounds__(kRelaxThreads) k_relax_tstar(RelaxArgs a, int round) {
   extern __shared__ double smem_d[];
-  __shared__ int s_flag, s_mask;
-  TileCtx c;
-  if (!tile_begin(a, round, &c, &s_flag)) return;
-  Smem s = carve(a, smem_d);
-  const int R = a.g.R, lw = a.g.lw, n = lw * a.g.lh, K = a.g.K, n_off = a.g.n_off;
+  __shared__ int s_flag, s_prob, s_mask, s_cnt[2];
+  const TileCtx c = tile_begin(a, round, &s_flag, &s_prob);
+  if (!c.active) return;
+  const Smem s = carve(a, smem_d);
+  const int R = a.R, lw = a.lw, n = lw * a.lh, n_off = a.n_off;
   const ProbDev pr = a.probs[c.p];
   if (!pr.tstar) return;  // block-uniform
-  const ProbDev pp = a.probs[pr.tstar_of];  // the propagation problem (pred source)
-  const double* WI = a.W + (int64_t)kFieldI * K * K * n_off;
-  if (threadIdx.x == 0) s_mask = 0;
-  load_classes(a, c, s.cls);
-  load_offsets(a, s.off);
+  const JobDev jb = a.jobs[pr.job];
+  const int K = jb.K;
+  if (threadIdx.x == 0) {
+    s_mask = 0;
+    s_cnt[0] = 0;
+    s_cnt[1] = 0;
+  }
+  load_common(a, c, jb, s);
   for (int q = threadIdx.x; q < n; q += blockDim.x) {
-    int64_t gx = c.x0 + (q % lw) - R, gz = c.z0 + (q / lw) - R;
-    bool in = gx >= 0 && gx < a.g.nx && gz >= 0 && gz < a.g.nz;
-    s.val[q] = in ? pr.tstar[gx + a.g.nx * gz] : NAN;
+    int gx = c.x0 + (q % lw) - R, gz = c.z0 + (q / lw) - R;
+    bool in = gx >= 0 && gx < jb.nx && gz >= 0 && gz < jb.nz;
+    int64_t g = (int64_t)gx + (int64_t)jb.nx * gz;
+    s.val[q] = in ? pr.tstar[g] : NAN;
+    // predecessor offset index of interior nodes (children); -1 elsewhere
+    bool inter = (q % lw) >= R && (q % lw) < R + c.txe && (q / lw) >= R && (q / lw) < R + c.tze;
+    s.ival[q] = inter ? pr.hop[g] : -1;
+  }
+  const double* WI = stage_w(a, jb, kFieldI, s);
+  __syncthreads();
+  const int ml = my_node(a, c);
+
+  {
+    bool known = false;
+    if (ml >= 0) {
+      const int o = s.ival[ml];
+      if (o >= 0 && isnan(s.val[ml])) {
+        const int ii = ml - s.off[o];
+        const double tp = s.val[ii];
+        if (!isnan(tp)) {
+          s.val[ml] = __dadd_rn(tp, WI[(s.cls[ii] * K + s.cls[ml]) * n_off + o]);
+          known = true;
+        }
+      }
+    }
+    frontier_add(known, ml, s.l0, &s_cnt[0]);
   }
   __syncthreads();
 
-  int li[kMaxNodesPerThread];
-  int32_t po[kMaxNodesPerThread];
-  int mine = 0;
-  for (int q = threadIdx.x; q < a.g.tx * a.g.tz && mine < kMaxNodesPerThread; q += blockDim.x) {
-    int x = q % a.g.tx, z = q / a.g.tx;
-    if (x >= c.txe || z >= c.tze) continue;
-    li[mine] = (z + R) * lw + (x + R);
-    po[mine] = pp.hop[(c.x0 + x) + a.g.nx * (c.z0 + z)];  // pred offset index
-    ++mine;
-  }
-  int it = 0, changed;
-  do {
-    changed = 0;
-    for (int m = 0; m < mine; ++m) {
-      const int l = li[m];
-      const int o = po[m];
-      if (o < 0 || !isnan(s.val[l])) continue;
-      const int ii = l - s.off[o];
-      const double tp = s.val[ii];
-      if (isnan(tp)) continue;
-      const int ki = s.cls[ii], kj = s.cls[l];
-      s.val[l] = __dadd_rn(tp, WI[((int64_t)ki * K + kj) * n_off + o]);
-      changed = 1;
-    }
-    ++it;
-  } while (__syncthreads_or(changed) && it < kLocalIterCap);
-
-  int mask = (it >= kLocalIterCap) ? (1 << 4) : 0;
-  for (int m = 0; m < mine; ++m) {
-    const int l = li[m];
-    if (po[m] >= 0 && !isnan(s.val[l])) {
-      int x = l % lw - R, z = l / lw - R;
-      int64_t g = (c.x0 + x) + a.g.nx * (c.z0 + z);
-      if (isnan(pr.tstar[g])) {
-        pr.tstar[g] = s.val[l];
-        mask |= border_bits(x, z, a.g.tx, a.g.tz, R);
+  const int q_step = kRelaxThreads / n_off, r_step = kRelaxThreads % n_off;
+  int cur = 0, it = 0;
+  int nf = s_cnt[0];
+  while (nf > 0 && it < kLocalIterCap) {
+    const int nxt = cur ^ 1;
+    int32_t* const lcur = cur ? s.l1 : s.l0;
+    int32_t* const lnxt = cur ? s.l0 : s.l1;
+    if (threadIdx.x == 0) s_cnt[nxt] = 0;
+    __syncthreads();
+    const int total = nf * n_off;
+    const int bound = uniform_bound(total);
+    int f = threadIdx.x / n_off, o = threadIdx.x % n_off;
+    for (int item = threadIdx.x; item < bound; item += kRelaxThreads) {
+      bool known = false;
+      int j = 0;
+      if (item < total) {
+        const int i = lcur[f];
+        j = i + s.off[o];
+        // j's predecessor is i (j - i = o; j interior).  One parent per
+        // child, so one writer; the NaN test skips children the pull already
+        // resolved, keeping every node in at most one frontier.
+        if (s.ival[j] == o && isnan(s.val[j])) {
+          s.val[j] = __dadd_rn(s.val[i], WI[(s.cls[i] * K + s.cls[j]) * n_off + o]);
+          known = true;
+        }
       }
+      frontier_add(known, j, lnxt, &s_cnt[nxt]);
+      f += q_step;
+      o += r_step;
+      if (o >= n_off) {
+        o -= n_off;
+        ++f;
+      }
+    }
+    __syncthreads();
+    nf = s_cnt[nxt];
+    cur = nxt;
+    ++it;
+    __syncthreads();
+  }
+
+  int mask = (nf > 0) ? (1 << 4) : 0;
+  if (ml >= 0 && s.ival[ml] >= 0 && !isnan(s.val[ml])) {
+    int x = ml % lw - R, z = ml / lw - R;
+    int64_t g = (int64_t)(c.x0 + x) + (int64_t)jb.nx * (c.z0 + z);
+    if (isnan(pr.tstar[g])) {
+      pr.tstar[g] = s.val[ml];
+      mask |= border_bits(x, z, a.tx, a.tz, R);
     }
   }
   if (mask) atomicOr(&s_mask, mask);
   __syncthreads();
-  if (threadIdx.x == 0 && s_mask) activate(a, round, c, s_mask);
+  if (threadIdx.x == 0 && s_mask) activate(a, round, c, pr, jb, s_mask);
 }
 
-// unreachable nodes: t* = +inf
-__global__ void k_tstar_finish(ProbDev* probs, int n_prob, int64_t n_nodes) {
-  int64_t total = (int64_t)n_prob * n_nodes;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    ProbDev pr = probs[t / n_nodes];
-    if (pr.tstar && isnan(pr.tstar[t % n_nodes])) pr.tstar[t % n_nodes] = INFINITY;
-  }
+// unreachable nodes: t* = +inf.  blockIdx.y = problem.
+__global__ void k_tstar_finish(const ProbDev* probs, const JobDev* jobs) {
+  const ProbDev pr = probs[blockIdx.y];
+  if (!pr.tstar) return;
+  const int64_t n = (int64_t)jobs[pr.job].nx * jobs[pr.job].nz;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x)
+    if (isnan(pr.tstar[j])) pr.tstar[j] = INFINITY;
 }
 
 // ----------------------------------------------------------- host side ---
 
-struct WsLayout {
-  size_t star, W, probs, flags, counter, err, hop, total;
-  int n_off, n_prob, n_tiles, max_rounds;
-};
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static int count_problems(uint32_t outs, int n_src) {
+static void tile_dims(const chert_trace_opts* o, int* tx, int* tz) {
+  *tx = (o && o->tile_x > 0) ? o->tile_x : 32;
+  *tz = (o && o->tile_z > 0) ? o->tile_z : 32;
+}
+
+static int problems_per_source(uint32_t outs) {
   int per = 0;
   if (outs & (CHERT_OUT_TAU_R | CHERT_OUT_PRED_P | CHERT_OUT_TSTAR)) ++per;
   if (outs & (CHERT_OUT_TAU_I | CHERT_OUT_PRED_A)) ++per;
-  return per * n_src;
+  return per;
 }
 
-static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+struct Plan {
+  int tx, tz, R, n_off, lw, lh;
+  int n_prob = 0;
+  int64_t n_tiles = 0;
+  int max_rounds = 0;
+  std::vector<int64_t> nodes;  // per job
+  std::vector<int> ntx, ntz, K;
+  size_t off_star = 0, off_lbin = 0, off_jobs = 0, off_probs = 0, off_flags = 0, off_counter = 0,
+         off_err = 0, off_hop = 0, total = 0;
+  std::vector<size_t> off_W;  // per job
+  int w_lds_doubles = 0;
+};
 
-static int tile_dims(const chert_trace_opts* o, int* tx, int* tz) {
-  *tx = (o && o->tile_x > 0) ? o->tile_x : 32;
-  *tz = (o && o->tile_z > 0) ? o->tile_z : 16;
-  return (*tx) * (*tz) <= kRelaxThreads * kMaxNodesPerThread;
-}
-
-static WsLayout ws_layout(int64_t K, const chert_grid* g, int n_src, const chert_trace_opts* o,
-                          int n_dirs) {
-  WsLayout L{};
-  int tx, tz;
-  tile_dims(o, &tx, &tz);
-  L.n_off = star_2d(g->radius, g->hx, g->hz, n_dirs, nullptr, nullptr, nullptr, nullptr);
-  L.n_prob = count_problems(o ? o->outputs : 0, n_src);
-  int ntx = (int)((g->nx + tx - 1) / tx), ntz = (int)((g->nz + tz - 1) / tz);
-  L.n_tiles = ntx * ntz;
-  L.max_rounds = (o && o->max_rounds > 0) ? o->max_rounds : 1024 + 64 * (ntx + ntz);
-  size_t off = 0;
-  L.star = off;
-  off += align256((size_t)kMaxOffsets * (3 * sizeof(int32_t) + sizeof(double)));
-  L.W = off;
-  off += align256((size_t)2 * K * K * L.n_off * sizeof(double));
-  L.probs = off;
-  off += align256((size_t)L.n_prob * sizeof(ProbDev));
-  L.flags = off;
-  off += align256((size_t)2 * L.n_prob * L.n_tiles * sizeof(int32_t));
-  L.counter = off;
-  off += align256((size_t)(L.max_rounds + 2) * sizeof(int32_t));
-  L.err = off;
-  off += 256;
-  L.hop = off;
-  off += align256((size_t)L.n_prob * g->nx * g->nz * sizeof(int32_t));
-  L.total = off;
-  return L;
-}
-
-static int validate(const chert_cache_desc* d, int64_t K, const chert_grid* g, int mode,
-                    int n_src, const chert_trace_opts* o) {
+static int validate_job(const chert_trace_job& j, uint32_t outs) {
   chert_cache_layout lay;
-  int rc = chert_cache_layout_of(d, K, &lay);
+  int rc = chert_cache_layout_of(j.d, j.n_classes, &lay);
   if (rc) return rc;
-  if (!g || !o) return fail(CHERT_ERR_INVALID_ARG, "null grid or options");
+  const chert_grid* g = j.g;
+  if (!g) return fail(CHERT_ERR_INVALID_ARG, "null grid");
   if (g->dim == 3) return fail(CHERT_ERR_UNSUPPORTED, "3D grids are not traced yet");
   if (g->dim != 2 || g->ny != 1) return fail(CHERT_ERR_INVALID_ARG, "2D grid needs dim 2, ny 1");
-  if (g->nx < 1 || g->nz < 1 || g->nx * g->nz > 0x7fffffffLL)
+  if (g->nx < 1 || g->nz < 1 || g->nx * g->nz >= 0x7fffffffLL)
     return fail(CHERT_ERR_INVALID_ARG, "grid size out of range");
-  if (g->radius < 1 || g->radius > kMaxRadius) return fail(CHERT_ERR_INVALID_ARG, "radius must be 1..8");
+  if (g->radius < 1 || g->radius > kMaxRadius)
+    return fail(CHERT_ERR_INVALID_ARG, "radius must be 1..8");
   if (!(g->hx > 0.0) || !(g->hz > 0.0) || !isfinite(g->hx) || !isfinite(g->hz))
     return fail(CHERT_ERR_INVALID_ARG, "spacing must be positive");
   if (!g->class_id_dev) return fail(CHERT_ERR_INVALID_ARG, "null class ids");
-  if (mode < 0 || mode > 2 || !(d->mode_mask & (1u << mode)))
+  if (j.mode < 0 || j.mode > 2 || !(j.d->mode_mask & (1u << j.mode)))
     return fail(CHERT_ERR_INVALID_ARG, "mode not in the cache");
-  if (n_src < 1) return fail(CHERT_ERR_INVALID_ARG, "need at least one source");
+  if (j.n_src < 1) return fail(CHERT_ERR_INVALID_ARG, "need at least one source");
+  if (!j.cache_dev) return fail(CHERT_ERR_INVALID_ARG, "null cache");
+  if (!j.src_nodes_host) return fail(CHERT_ERR_INVALID_ARG, "null sources");
+  const int64_t n = g->nx * g->nz;
+  for (int i = 0; i < j.n_src; ++i)
+    if (j.src_nodes_host[i] < 0 || j.src_nodes_host[i] >= n)
+      return fail(CHERT_ERR_INVALID_ARG, "source node out of range");
+  if (((outs & CHERT_OUT_TAU_R) && !j.tau_r_dev) || ((outs & CHERT_OUT_TAU_I) && !j.tau_i_dev) ||
+      ((outs & CHERT_OUT_TSTAR) && !j.tstar_dev) || ((outs & CHERT_OUT_PRED_P) && !j.pred_p_dev) ||
+      ((outs & CHERT_OUT_PRED_A) && !j.pred_a_dev))
+    return fail(CHERT_ERR_INVALID_ARG, "a selected output is NULL");
+  if ((int64_t)j.n_classes * j.n_classes > ((int64_t)1 << 26))
+    return fail(CHERT_ERR_UNSUPPORTED, "class-pair table too large");
+  return CHERT_OK;
+}
+
+static int validate_opts(const chert_trace_opts* o) {
+  if (!o) return fail(CHERT_ERR_INVALID_ARG, "null options");
   uint32_t outs = o->outputs;
   if (outs == 0 || (outs & ~31u)) return fail(CHERT_ERR_INVALID_ARG, "bad output mask");
   if ((outs & CHERT_OUT_TSTAR) && !((outs & CHERT_OUT_TAU_R) && (outs & CHERT_OUT_PRED_P)))
@@ -605,36 +778,83 @@ static int validate(const chert_cache_desc* d, int64_t K, const chert_grid* g, i
     return fail(CHERT_ERR_INVALID_ARG, "PRED_P needs TAU_R");
   if ((outs & CHERT_OUT_PRED_A) && !(outs & CHERT_OUT_TAU_I))
     return fail(CHERT_ERR_INVALID_ARG, "PRED_A needs TAU_I");
-  int tx, tz;
-  if (!tile_dims(o, &tx, &tz) || tx < g->radius || tz < g->radius)
-    return fail(CHERT_ERR_INVALID_ARG, "tile must hold >= radius and <= 1024 nodes");
   return CHERT_OK;
 }
 
-}  // namespace chert
-
-using namespace chert;
-
-extern "C" size_t chert_trace_workspace_bytes(const chert_cache_desc* d, int64_t n_classes,
-                                              const chert_grid* g, int32_t n_src,
-                                              const chert_trace_opts* o) {
-  if (!d || !g || !o) return 0;
-  int mode = (d->mode_mask & 1u) ? 0 : ((d->mode_mask & 2u) ? 1 : 2);
-  if (validate(d, n_classes, g, mode, n_src, o) != CHERT_OK) return 0;
-  return ws_layout(n_classes, g, n_src, o, d->n_dirs).total;
+static int make_plan(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o,
+                     Plan* P) {
+  if (!jobs || n_jobs < 1) return fail(CHERT_ERR_INVALID_ARG, "need at least one job");
+  int rc = validate_opts(o);
+  if (rc) return rc;
+  for (int j = 0; j < n_jobs; ++j) {
+    rc = validate_job(jobs[j], o->outputs);
+    if (rc) return rc;
+    if (jobs[j].g->radius != jobs[0].g->radius)
+      return fail(CHERT_ERR_INVALID_ARG, "all jobs of a batch need the same radius");
+  }
+  tile_dims(o, &P->tx, &P->tz);
+  P->R = jobs[0].g->radius;
+  if (P->tx < P->R || P->tz < P->R || P->tx * P->tz > kRelaxThreads)
+    return fail(CHERT_ERR_INVALID_ARG, "tile must be >= radius per side and <= 1024 nodes");
+  P->n_off = star_2d(P->R, 1.0, 1.0, 4, nullptr, nullptr, nullptr, nullptr);
+  P->lw = P->tx + 2 * P->R;
+  P->lh = P->tz + 2 * P->R;
+  const int per = problems_per_source(o->outputs);
+  int64_t max_tile_span = 0, prob_nodes = 0;
+  int w_lds = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    const chert_grid* g = jobs[j].g;
+    int ntx = (int)((g->nx + P->tx - 1) / P->tx), ntz = (int)((g->nz + P->tz - 1) / P->tz);
+    P->ntx.push_back(ntx);
+    P->ntz.push_back(ntz);
+    P->K.push_back((int)jobs[j].n_classes);
+    P->nodes.push_back(g->nx * g->nz);
+    int np = per * jobs[j].n_src;
+    P->n_prob += np;
+    P->n_tiles += (int64_t)np * ntx * ntz;
+    prob_nodes += (int64_t)np * g->nx * g->nz;
+    if (ntx + ntz > max_tile_span) max_tile_span = ntx + ntz;
+    size_t wf = (size_t)jobs[j].n_classes * jobs[j].n_classes * P->n_off * sizeof(double);
+    if (wf <= kWLdsBytes && (int)(wf / sizeof(double)) > w_lds) w_lds = (int)(wf / sizeof(double));
+  }
+  if (P->n_tiles >= 0x7fffffffLL || P->n_prob > 65535)
+    return fail(CHERT_ERR_UNSUPPORTED, "batch too large for one launch");
+  P->w_lds_doubles = w_lds;
+  P->max_rounds = (o->max_rounds > 0) ? o->max_rounds : 1024 + 64 * (int)max_tile_span;
+  size_t off = 0;
+  P->off_star = off;
+  off += align256((size_t)kMaxOffsets * 2 * sizeof(int32_t));
+  P->off_lbin = off;
+  off += align256((size_t)n_jobs * kMaxOffsets * (sizeof(double) + sizeof(int32_t)));
+  P->off_jobs = off;
+  off += align256((size_t)n_jobs * sizeof(JobDev));
+  P->off_probs = off;
+  off += align256((size_t)P->n_prob * sizeof(ProbDev));
+  P->off_flags = off;
+  off += align256((size_t)2 * P->n_tiles * sizeof(int32_t));
+  P->off_counter = off;
+  off += align256((size_t)(P->max_rounds + 2) * sizeof(int32_t));
+  P->off_err = off;
+  off += 256;
+  for (int j = 0; j < n_jobs; ++j) {
+    P->off_W.push_back(off);
+    off += align256((size_t)2 * jobs[j].n_classes * jobs[j].n_classes * P->n_off * sizeof(double));
+  }
+  P->off_hop = off;
+  off += align256((size_t)prob_nodes * sizeof(int32_t));
+  P->total = off;
+  return CHERT_OK;
 }
 
 static int run_rounds(hipStream_t s, const RelaxArgs& a, void (*kern)(RelaxArgs, int),
                       size_t lds, int max_rounds) {
-  const int n_tiles = a.g.ntx * a.g.ntz;
-  const int64_t grid = (int64_t)a.n_prob * n_tiles;
   const int batch = 8;
   int32_t counts[batch];
   for (int r = 0; r < max_rounds; r += batch) {
     int nb = batch;
     if (r + nb > max_rounds) nb = max_rounds - r;
     for (int q = 0; q < nb; ++q)
-      hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kRelaxThreads), lds, s, a, r + q);
+      hipLaunchKernelGGL(kern, dim3((unsigned)a.n_tiles), dim3(kRelaxThreads), lds, s, a, r + q);
     hipError_t e = hipMemcpyAsync(counts, a.counter + r + 1, sizeof(int32_t) * nb,
                                   hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -645,162 +865,158 @@ static int run_rounds(hipStream_t s, const RelaxArgs& a, void (*kern)(RelaxArgs,
   return fail(CHERT_ERR_NO_CONVERGENCE, "relaxation round cap reached");
 }
 
-extern "C" int chert_trace_field(const chert_cache_desc* d, const void* cache_dev,
-                                 int64_t n_classes, const chert_grid* g, int32_t mode,
-                                 const int64_t* src_nodes_host, int32_t n_src,
-                                 const chert_trace_opts* o, double* tau_r_dev,
-                                 double* tau_i_dev, double* tstar_dev, int32_t* pred_p_dev,
-                                 int32_t* pred_a_dev, void* workspace_dev,
-                                 size_t workspace_bytes, void* stream) {
-  int rc = validate(d, n_classes, g, mode, n_src, o);
+static int trace_batch(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o,
+                       void* workspace_dev, size_t workspace_bytes, hipStream_t s) {
+  Plan P;
+  int rc = make_plan(jobs, n_jobs, o, &P);
   if (rc) return rc;
-  if (!cache_dev) return fail(CHERT_ERR_INVALID_ARG, "null cache");
-  if (!src_nodes_host) return fail(CHERT_ERR_INVALID_ARG, "null sources");
-  const int64_t n_nodes = g->nx * g->nz;
-  for (int i = 0; i < n_src; ++i)
-    if (src_nodes_host[i] < 0 || src_nodes_host[i] >= n_nodes)
-      return fail(CHERT_ERR_INVALID_ARG, "source node out of range");
-  const uint32_t outs = o->outputs;
-  if (((outs & CHERT_OUT_TAU_R) && !tau_r_dev) || ((outs & CHERT_OUT_TAU_I) && !tau_i_dev) ||
-      ((outs & CHERT_OUT_TSTAR) && !tstar_dev) || ((outs & CHERT_OUT_PRED_P) && !pred_p_dev) ||
-      ((outs & CHERT_OUT_PRED_A) && !pred_a_dev))
-    return fail(CHERT_ERR_INVALID_ARG, "a selected output is NULL");
-  const int64_t K = n_classes;
-  WsLayout L = ws_layout(K, g, n_src, o, d->n_dirs);
-  if (!workspace_dev || workspace_bytes < L.total)
+  if (!workspace_dev || workspace_bytes < P.total)
     return fail(CHERT_ERR_INVALID_ARG, "workspace too small");
-  if (K * K * (int64_t)L.n_off > (int64_t)1 << 28)
-    return fail(CHERT_ERR_UNSUPPORTED, "class-pair table too large");
-
-  hipStream_t s = (hipStream_t)stream;
   uint8_t* ws = (uint8_t*)workspace_dev;
-  chert_cache_layout lay;
-  chert_cache_layout_of(d, K, &lay);
-  const uint8_t* cache = (const uint8_t*)cache_dev;
-  const int64_t ent = 3 * K * (int64_t)d->n_dirs;
-  const int64_t mslice = (int64_t)mode * K * d->n_dirs;
-  const double* fields = (const double*)(cache + lay.fields_offset);
-  const double* Vm = fields + CHERT_F_V * ent + mslice;
-  const double* Am = fields + CHERT_F_A * ent + mslice;
-  const int32_t* Sm = (const int32_t*)(cache + lay.status_offset) + mslice;
+  const uint32_t outs = o->outputs;
 
-  // forward star on the host (IEEE sqrt/atan2), uploaded once per call
-  std::vector<uint8_t> star(align256((size_t)kMaxOffsets * (3 * sizeof(int32_t) + sizeof(double))));
-  int32_t* hox = (int32_t*)star.data();
-  int32_t* hoz = hox + kMaxOffsets;
-  int32_t* hbin = hoz + kMaxOffsets;
-  double* hL = (double*)(hbin + kMaxOffsets);
-  star_2d(g->radius, g->hx, g->hz, d->n_dirs, hox, hoz, hL, hbin);
-  int32_t* dox = (int32_t*)(ws + L.star);
+  // forward star (shared offsets) and per-job lengths/bins on the host
+  std::vector<int32_t> star(2 * kMaxOffsets);
+  std::vector<uint8_t> lbin((size_t)n_jobs * kMaxOffsets * (sizeof(double) + sizeof(int32_t)));
+  double* hL = (double*)lbin.data();
+  int32_t* hbin = (int32_t*)(hL + (size_t)n_jobs * kMaxOffsets);
+  for (int j = 0; j < n_jobs; ++j) {
+    const chert_grid* g = jobs[j].g;
+    star_2d(P.R, g->hx, g->hz, jobs[j].d->n_dirs, star.data(), star.data() + kMaxOffsets,
+            hL + (size_t)j * kMaxOffsets, hbin + (size_t)j * kMaxOffsets);
+  }
+  int32_t* dox = (int32_t*)(ws + P.off_star);
   int32_t* doz = dox + kMaxOffsets;
-  int32_t* dbin = doz + kMaxOffsets;
-  double* dL = (double*)(dbin + kMaxOffsets);
+  double* dL = (double*)(ws + P.off_lbin);
+  int32_t* dbin = (int32_t*)(dL + (size_t)n_jobs * kMaxOffsets);
 
-  // problems: per source, propagation then attenuation
+  std::vector<JobDev> jd(n_jobs);
   std::vector<ProbDev> probs;
-  int32_t* hop = (int32_t*)(ws + L.hop);
-  for (int i = 0; i < n_src; ++i) {
-    int prop_idx = -1;
-    if (outs & (CHERT_OUT_TAU_R | CHERT_OUT_PRED_P | CHERT_OUT_TSTAR)) {
-      ProbDev p{};
-      p.tau = tau_r_dev + (int64_t)i * n_nodes;
-      p.pred = (outs & CHERT_OUT_PRED_P) ? pred_p_dev + (int64_t)i * n_nodes : nullptr;
-      p.tstar = (outs & CHERT_OUT_TSTAR) ? tstar_dev + (int64_t)i * n_nodes : nullptr;
-      p.src = src_nodes_host[i];
-      p.field = kFieldR;
-      prop_idx = (int)probs.size();
-      p.tstar_of = prop_idx;
-      p.hop = hop + (int64_t)probs.size() * n_nodes;
-      probs.push_back(p);
-    }
-    if (outs & (CHERT_OUT_TAU_I | CHERT_OUT_PRED_A)) {
-      ProbDev p{};
-      p.tau = tau_i_dev + (int64_t)i * n_nodes;
-      p.pred = (outs & CHERT_OUT_PRED_A) ? pred_a_dev + (int64_t)i * n_nodes : nullptr;
-      p.tstar = nullptr;
-      p.src = src_nodes_host[i];
-      p.field = kFieldI;
-      p.tstar_of = -1;
-      p.hop = hop + (int64_t)probs.size() * n_nodes;
-      probs.push_back(p);
+  int32_t* hop = (int32_t*)(ws + P.off_hop);
+  int64_t hop_off = 0;
+  int tile_base = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    const chert_trace_job& J = jobs[j];
+    JobDev& d = jd[j];
+    d.nx = (int)J.g->nx;
+    d.nz = (int)J.g->nz;
+    d.ntx = P.ntx[j];
+    d.ntz = P.ntz[j];
+    d.K = P.K[j];
+    size_t wf = (size_t)d.K * d.K * P.n_off;
+    d.w_in_lds = (wf <= (size_t)P.w_lds_doubles) ? 1 : 0;
+    d.class_id = J.g->class_id_dev;
+    d.W = (const double*)(ws + P.off_W[j]);
+    const int64_t n = P.nodes[j];
+    const int ntiles = d.ntx * d.ntz;
+    for (int i = 0; i < J.n_src; ++i) {
+      if (outs & (CHERT_OUT_TAU_R | CHERT_OUT_PRED_P | CHERT_OUT_TSTAR)) {
+        ProbDev p{};
+        p.tau = J.tau_r_dev + (int64_t)i * n;
+        p.pred = (outs & CHERT_OUT_PRED_P) ? J.pred_p_dev + (int64_t)i * n : nullptr;
+        p.tstar = (outs & CHERT_OUT_TSTAR) ? J.tstar_dev + (int64_t)i * n : nullptr;
+        p.src = J.src_nodes_host[i];
+        p.job = j;
+        p.field = kFieldR;
+        p.tile_base = tile_base;
+        p.hop = hop + hop_off;
+        hop_off += n;
+        tile_base += ntiles;
+        probs.push_back(p);
+      }
+      if (outs & (CHERT_OUT_TAU_I | CHERT_OUT_PRED_A)) {
+        ProbDev p{};
+        p.tau = J.tau_i_dev + (int64_t)i * n;
+        p.pred = (outs & CHERT_OUT_PRED_A) ? J.pred_a_dev + (int64_t)i * n : nullptr;
+        p.tstar = nullptr;
+        p.src = J.src_nodes_host[i];
+        p.job = j;
+        p.field = kFieldI;
+        p.tile_base = tile_base;
+        p.hop = hop + hop_off;
+        hop_off += n;
+        tile_base += ntiles;
+        probs.push_back(p);
+      }
     }
   }
-  ProbDev* dprobs = (ProbDev*)(ws + L.probs);
-  hipError_t e = hipMemcpyAsync(dox, star.data(), star.size(), hipMemcpyHostToDevice, s);
+  JobDev* djobs = (JobDev*)(ws + P.off_jobs);
+  ProbDev* dprobs = (ProbDev*)(ws + P.off_probs);
+  hipError_t e = hipMemcpyAsync(dox, star.data(), star.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dL, lbin.data(), lbin.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(dprobs, probs.data(), probs.size() * sizeof(ProbDev), hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(djobs, jd.data(), jd.size() * sizeof(JobDev), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dprobs, probs.data(), probs.size() * sizeof(ProbDev),
+                       hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // host buffers are locals
   if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
 
-  Geom G{};
-  G.nx = g->nx;
-  G.nz = g->nz;
-  tile_dims(o, &G.tx, &G.tz);
-  G.ntx = (int)((g->nx + G.tx - 1) / G.tx);
-  G.ntz = (int)((g->nz + G.tz - 1) / G.tz);
-  G.R = g->radius;
-  G.n_off = L.n_off;
-  G.lw = G.tx + 2 * G.R;
-  G.lh = G.tz + 2 * G.R;
-  G.K = (int)K;
-
   RelaxArgs a{};
-  a.g = G;
-  a.class_id = g->class_id_dev;
+  a.tx = P.tx;
+  a.tz = P.tz;
+  a.R = P.R;
+  a.n_off = P.n_off;
+  a.lw = P.lw;
+  a.lh = P.lh;
+  a.n_prob = P.n_prob;
+  a.n_tiles = (int)P.n_tiles;
+  a.jobs = djobs;
+  a.probs = dprobs;
   a.ox = dox;
   a.oz = doz;
-  a.W = (const double*)(ws + L.W);
-  a.probs = dprobs;
-  a.n_prob = (int)probs.size();
-  a.flags = (int32_t*)(ws + L.flags);
-  a.counter = (int32_t*)(ws + L.counter);
-  a.err = (int32_t*)(ws + L.err);
-  const size_t lds_base = (size_t)G.lw * G.lh * (sizeof(double) + 2 * sizeof(int32_t)) +
-                          sizeof(int32_t) * ((G.n_off + 1) & ~1);
-  const size_t wbytes = (size_t)K * K * G.n_off * sizeof(double);
-  a.w_in_lds = (lds_base + wbytes <= 48 * 1024) ? 1 : 0;
-  const size_t lds = lds_base + (a.w_in_lds ? wbytes : 0);
+  a.flags = (int32_t*)(ws + P.off_flags);
+  a.counter = (int32_t*)(ws + P.off_counter);
+  a.err = (int32_t*)(ws + P.off_err);
+  a.w_lds_doubles = P.w_lds_doubles;
+  const size_t lds = lds_bytes(P.lw, P.lh, P.w_lds_doubles, P.n_off, P.tx, P.tz);
 
-  {
-    int64_t tw = 2 * K * K * G.n_off;
+  for (int j = 0; j < n_jobs; ++j) {
+    const chert_trace_job& J = jobs[j];
+    chert_cache_layout lay;
+    chert_cache_layout_of(J.d, J.n_classes, &lay);
+    const uint8_t* cache = (const uint8_t*)J.cache_dev;
+    const int64_t K = J.n_classes;
+    const int64_t ent = 3 * K * (int64_t)J.d->n_dirs;
+    const int64_t mslice = (int64_t)J.mode * K * J.d->n_dirs;
+    const double* fields = (const double*)(cache + lay.fields_offset);
+    const double* Vm = fields + CHERT_F_V * ent + mslice;
+    const double* Am = fields + CHERT_F_A * ent + mslice;
+    const int32_t* Sm = (const int32_t*)(cache + lay.status_offset) + mslice;
+    int64_t tw = 2 * K * K * P.n_off;
     int64_t blocks = (tw + 255) / 256;
     hipLaunchKernelGGL(k_weights, dim3((unsigned)(blocks > 65536 ? 65536 : blocks)), dim3(256),
-                       0, s, (double*)(ws + L.W), (int)K, G.n_off, Vm, Am, Sm, d->n_dirs, dL,
-                       dbin);
-    int64_t tn = (int64_t)a.n_prob * n_nodes;
-    int64_t nb = (tn + 255) / 256;
-    hipLaunchKernelGGL(k_init_fields, dim3((unsigned)(nb > 65536 ? 65536 : nb)), dim3(256), 0, s,
-                       dprobs, a.n_prob, n_nodes, a.err);
+                       0, s, (double*)(ws + P.off_W[j]), (int)K, P.n_off, Vm, Am, Sm,
+                       J.d->n_dirs, dL + (size_t)j * kMaxOffsets, dbin + (size_t)j * kMaxOffsets);
   }
-  const int64_t n_flags = 2LL * a.n_prob * L.n_tiles;
+  int64_t max_nodes = 0;
+  for (int64_t n : P.nodes) max_nodes = n > max_nodes ? n : max_nodes;
+  const unsigned gx = (unsigned)((max_nodes + 255) / 256 > 1024 ? 1024 : (max_nodes + 255) / 256);
+  const dim3 pgrid(gx, (unsigned)P.n_prob);
+  hipLaunchKernelGGL(k_init_fields, pgrid, dim3(256), 0, s, dprobs, djobs, a.err);
+  const int64_t n_flags = 2 * P.n_tiles;
   auto init_flags = [&](int tstar_phase) {
-    hipLaunchKernelGGL(k_init_flags, dim3(64), dim3(256), 0, s, a.flags, n_flags, a.counter,
-                       L.max_rounds + 2);
-    hipLaunchKernelGGL(k_seed_flags, dim3((a.n_prob + 63) / 64), dim3(64), 0, s, a.flags,
-                       a.counter, dprobs, a.n_prob, G, tstar_phase);
+    hipLaunchKernelGGL(k_clear_flags, dim3(256), dim3(256), 0, s, a.flags, n_flags, a.counter,
+                       P.max_rounds + 2);
+    hipLaunchKernelGGL(k_seed_flags, dim3((P.n_prob + 63) / 64), dim3(64), 0, s, a.flags,
+                       a.counter, dprobs, djobs, P.n_prob, P.tx, P.tz, tstar_phase);
   };
   init_flags(0);
-  rc = run_rounds(s, a, k_relax_tau, lds, L.max_rounds);
+  rc = run_rounds(s, a, k_relax_tau, lds, P.max_rounds);
   if (rc) return rc;
-  bool need_pred = (outs & (CHERT_OUT_PRED_P | CHERT_OUT_PRED_A)) != 0;
-  if (need_pred) {
+  if (outs & (CHERT_OUT_PRED_P | CHERT_OUT_PRED_A)) {
     init_flags(0);
-    rc = run_rounds(s, a, k_relax_hop, lds, L.max_rounds);
+    rc = run_rounds(s, a, k_relax_hop, lds, P.max_rounds);
     if (rc) return rc;
-    int64_t tn = (int64_t)a.n_prob * n_nodes;
-    int64_t nb = (tn + 255) / 256;
-    unsigned gb = (unsigned)(nb > 65536 ? 65536 : nb);
-    hipLaunchKernelGGL(k_pred, dim3(gb), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_pred_offsets, dim3(gb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_pred, pgrid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_pred_offsets, pgrid, dim3(256), 0, s, a);
   }
   if (outs & CHERT_OUT_TSTAR) {
     init_flags(1);
-    rc = run_rounds(s, a, k_relax_tstar, lds, L.max_rounds);
+    rc = run_rounds(s, a, k_relax_tstar, lds, P.max_rounds);
     if (rc) return rc;
-    int64_t tn = (int64_t)a.n_prob * n_nodes;
-    int64_t nb = (tn + 255) / 256;
-    hipLaunchKernelGGL(k_tstar_finish, dim3((unsigned)(nb > 65536 ? 65536 : nb)), dim3(256), 0,
-                       s, dprobs, a.n_prob, n_nodes);
+    hipLaunchKernelGGL(k_tstar_finish, pgrid, dim3(256), 0, s, dprobs, djobs);
   }
   int32_t herr = 0;
   e = hipMemcpyAsync(&herr, a.err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
@@ -808,4 +1024,70 @@ extern "C" int chert_trace_field(const chert_cache_desc* d, const void* cache_de
   if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
   if (herr) return fail(CHERT_ERR_INVALID_ARG, "class id out of range");
   return CHERT_OK;
+}
+
+static chert_trace_job single_job(const chert_cache_desc* d, const void* cache_dev,
+                                  int64_t n_classes, const chert_grid* g, int32_t mode,
+                                  const int64_t* src, int32_t n_src, double* tau_r,
+                                  double* tau_i, double* tstar, int32_t* pred_p,
+                                  int32_t* pred_a) {
+  chert_trace_job j{};
+  j.d = d;
+  j.cache_dev = cache_dev;
+  j.n_classes = n_classes;
+  j.g = g;
+  j.mode = mode;
+  j.src_nodes_host = src;
+  j.n_src = n_src;
+  j.tau_r_dev = tau_r;
+  j.tau_i_dev = tau_i;
+  j.tstar_dev = tstar;
+  j.pred_p_dev = pred_p;
+  j.pred_a_dev = pred_a;
+  return j;
+}
+
+}  // namespace chert
+
+using namespace chert;
+
+extern "C" size_t chert_trace_batch_workspace_bytes(const chert_trace_job* jobs, int32_t n_jobs,
+                                                    const chert_trace_opts* o) {
+  Plan P;
+  if (make_plan(jobs, n_jobs, o, &P) != CHERT_OK) return 0;
+  return P.total;
+}
+
+extern "C" int chert_trace_batch(const chert_trace_job* jobs, int32_t n_jobs,
+                                 const chert_trace_opts* o, void* workspace_dev,
+                                 size_t workspace_bytes, void* stream) {
+  return trace_batch(jobs, n_jobs, o, workspace_dev, workspace_bytes, (hipStream_t)stream);
+}
+
+extern "C" size_t chert_trace_workspace_bytes(const chert_cache_desc* d, int64_t n_classes,
+                                              const chert_grid* g, int32_t n_src,
+                                              const chert_trace_opts* o) {
+  if (!d || !g || !o) return 0;
+  // sizes only: placeholders stand in for the device pointers and sources
+  std::vector<int64_t> src((size_t)(n_src > 0 ? n_src : 0), 0);
+  int mode = (d->mode_mask & 1u) ? 0 : ((d->mode_mask & 2u) ? 1 : 2);
+  double dummy_d = 0.0;
+  int32_t dummy_i = 0;
+  chert_trace_job j = single_job(d, &dummy_d, n_classes, g, mode, src.data(), n_src, &dummy_d,
+                                 &dummy_d, &dummy_d, &dummy_i, &dummy_i);
+  Plan P;
+  if (make_plan(&j, 1, o, &P) != CHERT_OK) return 0;
+  return P.total;
+}
+
+extern "C" int chert_trace_field(const chert_cache_desc* d, const void* cache_dev,
+                                 int64_t n_classes, const chert_grid* g, int32_t mode,
+                                 const int64_t* src_nodes_host, int32_t n_src,
+                                 const chert_trace_opts* o, double* tau_r_dev,
+                                 double* tau_i_dev, double* tstar_dev, int32_t* pred_p_dev,
+                                 int32_t* pred_a_dev, void* workspace_dev,
+                                 size_t workspace_bytes, void* stream) {
+  chert_trace_job j = single_job(d, cache_dev, n_classes, g, mode, src_nodes_host, n_src,
+                                 tau_r_dev, tau_i_dev, tstar_dev, pred_p_dev, pred_a_dev);
+  return trace_batch(&j, 1, o, workspace_dev, workspace_bytes, (hipStream_t)stream);
 }

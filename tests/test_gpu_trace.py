@@ -154,3 +154,45 @@ def test_invalid_class_id_reported(G):
     with pytest.raises(Cm.ChertError) as e:
         G.trace(cache, desc, cls.shape[0], m.nx, m.nz, m.hx, m.hz, m.radius, cid, 0, m.sources)
     assert e.value.code == 1
+
+
+def test_batch_uneven_grids_modes_sources_bitwise(G):
+    """chert_trace_batch: two grids of different size and class count, two
+    modes each, several sources -> every field bitwise equal to the oracle."""
+    import torch
+    Cm = C()
+    m1 = W.small_layered(nx=61, nz=35, radius=3, seed=21)
+    m2 = W.small_layered(nx=29, nz=47, n_layers=4, radius=3, seed=22)
+    jobs = []
+    b = Cm.Batch()
+    keep = []
+    for mdl, srcs in ((m1, [0, 61 * 35 - 1, 30 + 61 * 17]), (m2, [5, 28 + 29 * 40])):
+        cls, f, s = oracle_cache(mdl, (0, 1), n_sweep=720)
+        K = cls.shape[0]
+        desc = Cm.cache_desc(n_dirs=360, modes=(0, 1), n_sweep=720)
+        cache = G.import_cache(f, s, desc, K)
+        cid = torch.from_numpy(mdl.class_id.reshape(-1).astype(np.int32)).to(G.DEV)
+        grid = Cm.make_grid(mdl.nx, mdl.nz, mdl.hx, mdl.hz, mdl.radius, cid)
+        for mode in (0, 1):
+            n = mdl.n_nodes
+            out = dict(tau_r=torch.empty((len(srcs), n), dtype=torch.float64, device=G.DEV),
+                       tau_i=torch.empty((len(srcs), n), dtype=torch.float64, device=G.DEV),
+                       tstar=torch.empty((len(srcs), n), dtype=torch.float64, device=G.DEV),
+                       pred_p=torch.empty((len(srcs), n), dtype=torch.int32, device=G.DEV),
+                       pred_a=torch.empty((len(srcs), n), dtype=torch.int32, device=G.DEV))
+            b.add(desc, cache, K, grid, mode, srcs, **out)
+            jobs.append((mdl, f, s, mode, srcs, out))
+        keep += [cache, cid, grid, desc]
+    opts = Cm.trace_opts(Cm.OUT_ALL)
+    ws = torch.empty(Cm.chert_trace_batch_workspace_bytes(b, opts), dtype=torch.uint8,
+                     device=G.DEV)
+    Cm.chert_trace_batch(b, opts, ws)
+    torch.cuda.synchronize()
+    for mdl, f, s, mode, srcs, out in jobs:
+        g = {"tauR": out["tau_r"].cpu().numpy(), "tauI": out["tau_i"].cpu().numpy(),
+             "tstar": out["tstar"].cpu().numpy(), "predP": out["pred_p"].cpu().numpy(),
+             "predA": out["pred_a"].cpu().numpy()}
+        for si, src in enumerate(srcs):
+            o = O.trace_2d(mdl.nx, mdl.nz, mdl.hx, mdl.hz, mdl.class_id, mdl.radius,
+                           f[0, mode], f[1, mode], s[mode], src)
+            assert_fields_equal(g, o, si)

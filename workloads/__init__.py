@@ -7,7 +7,7 @@ use it.  Every generator is deterministic for a given seed
 (numpy PCG64 with seed = 26108 * 10 + config number by default).
 
 The configurations stand in for the paper's workloads, which are not
-available (see DESIGN.md): config 1 is a homogeneous TTI block, config 2 the
+available: config 1 is a homogeneous TTI block, config 2 the
 layered controlled benchmark, config 3 the structurally complex 2D model.
 """
 from __future__ import annotations
