@@ -29,6 +29,35 @@ sys.path.insert(0, ROOT)
 METRIC = "Hamiltonian solves/s; edge relaxations/s; shots/s, surrogate vs plain at 1e-4"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP64_VALU_PEAK_TOPS = 39.3  # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz, one op per lane-cycle
+
+# HBM traffic per dispatch of the relaxation kernels on this workload, from
+# rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of
+# `bench.py --profile-steps 2` (see profiles/), scaled by what the same
+# counters read for a 256 MiB device copy (FETCH_SIZE x2.0, WRITE_SIZE x1.0).
+# Valid only for the kernel source it was measured on.
+MEASURED_TRAFFIC = {
+    "source": "paper_2609_26108_amd/csrc/trace.hip",
+    "source_sha256_16": "ed2cbc29a0e6d6f1",
+    "fetch_scale": 2.0, "write_scale": 1.0,
+    "kib_per_dispatch": {  # kernel -> (FETCH_SIZE KiB, WRITE_SIZE KiB)
+        "k_relax_tau": (2417.1, 728.0),
+        "k_relax_hop": (3030.8, 230.2),
+        "k_relax_tstar": (1557.4, 172.6),
+    },
+}
+
+
+def measured_traffic_bytes(kernel):
+    """Calibrated HBM bytes per dispatch, or None if not measured for the
+    current kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, MEASURED_TRAFFIC["source"])
+    h = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    kib = MEASURED_TRAFFIC["kib_per_dispatch"].get(kernel)
+    if kib is None or h != MEASURED_TRAFFIC["source_sha256_16"]:
+        return None
+    return 1024.0 * (kib[0] * MEASURED_TRAFFIC["fetch_scale"] + kib[1] * MEASURED_TRAFFIC["write_scale"])
 
 
 def useful_edges(nx, nz, ox, oz):
@@ -45,6 +74,11 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--profile-steps", type=int, default=0,
                    help="run only this many steps, no baseline (for rocprofv3)")
+    p.add_argument("--tile", type=int, nargs=2, default=(0, 0), metavar=("TX", "TZ"),
+                   help="relaxation tile shape (0 0 = library default)")
+    p.add_argument("--push-group", type=int, default=0, help="offsets per push item (1, 2, 4)")
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="only run 4 device-to-device copies of MIB MiB (HBM counter scale)")
     return p.parse_args()
 
 
@@ -62,6 +96,17 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        # a plain copy of known size: FETCH_SIZE/WRITE_SIZE per dispatch of
+        # this kernel against its true byte count gives the counter scale
+        n = args.copy_calibration * (1 << 20)
+        src = torch.ones(n, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n, "copies": 4}))
+        return
     m = W.config2()
     K = len(m.layers)
     desc = C.cache_desc(n_dirs=m.n_dirs, modes=m.modes)
@@ -73,7 +118,9 @@ def main():
     cws = torch.empty(max(C.chert_build_cache_workspace_bytes(desc, K), 1), dtype=torch.uint8,
                       device=dev)
     grid = C.make_grid(m.nx, m.nz, m.hx, m.hz, m.radius, cid)
-    opts = C.trace_opts(C.OUT_ALL)
+    stats = C.TraceStats()
+    opts = C.trace_opts(C.OUT_ALL, tile_x=args.tile[0], tile_z=args.tile[1], stats=stats,
+                        push_group=args.push_group)
     S = len(m.sources)
     n = m.n_nodes
     outs = {mode: dict(
@@ -114,14 +161,24 @@ def main():
         print(json.dumps({"profile_steps": args.profile_steps}))
         return
 
-    for _ in range(args.warmup):
+    # warmup; its last step is profiled for every kernel to find the
+    # dominant one
+    for w in range(max(args.warmup, 1)):
+        if w == max(args.warmup, 1) - 1:
+            C.chert_prof_enable(True)
         step()
     torch.cuda.synchronize()
+    prof_all = C.chert_prof_read()
+    dom = max(prof_all, key=lambda k: prof_all[k][1])
+    # timed region: HIP events bracket only the dominant kernel's launches
+    C.chert_prof_enable(True, only=dom)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step(timed=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    prof = C.chert_prof_read()
+    C.chert_prof_enable(False)
     ms = 1e3 * wall / args.steps
 
     ox, oz, L, b = C.chert_star_2d(m.radius, m.hx, m.hz, m.n_dirs)
@@ -137,6 +194,34 @@ def main():
     if not np.isfinite(tr):
         raise RuntimeError("bench produced an unreachable far corner")
 
+    kernels = {k: {"launches_per_step": v[0], "ms_per_step": v[1],
+                   "avg_us": 1e3 * v[1] / max(v[0], 1)} for k, v in prof_all.items()}
+    kernels[dom] = {"launches_per_step": prof[dom][0] / args.steps,
+                    "ms_per_step": prof[dom][1] / args.steps,
+                    "avg_us": 1e3 * prof[dom][1] / max(prof[dom][0], 1),
+                    "timed_region": True}
+    st = stats.as_dict()
+    raw = st["edge_relaxations"]
+    # Roofline of the dominant kernel.  The relaxation on a class cache keeps
+    # tau tiles, class ids and the class-pair weight table on chip, so its
+    # algorithmic work is FP64 VALU: one add and one compare per useful edge
+    # relaxation; peak = 78.6 TFLOP/s (FMA counted twice) / 2 = 39.3 T ops/s.
+    if dom.startswith("k_relax"):
+        phase = {"k_relax_tau": 0, "k_relax_hop": 1, "k_relax_tstar": 2}[dom]
+        useful_phase = {0: edges_per_step, 1: edges_per_step, 2: E * len(m.modes)}[phase]
+        per_launch_ops = 2.0 * useful_phase / kernels[dom]["launches_per_step"]
+        achieved = per_launch_ops / (kernels[dom]["avg_us"] * 1e-6) / 1e12
+        traffic = measured_traffic_bytes(dom)
+        roof = {"kernel": dom, "bound": "alu", "achieved": achieved,
+                "peak": FP64_VALU_PEAK_TOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_VALU_PEAK_TOPS, "traffic": traffic,
+                "work_per_launch": f"{per_launch_ops:.4g} FP64 ops (2 per useful edge)",
+                "avg_launch_us": kernels[dom]["avg_us"],
+                "hbm_gbs_measured": (traffic / (kernels[dom]["avg_us"] * 1e-6) / 1e9
+                                     if traffic else None)}
+    else:
+        roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": 78.6,
+                "unit": "TFLOP/s", "frac": None, "traffic": None}
     res = {
         "metric": METRIC,
         "value": edges_per_step / (wall / args.steps),
@@ -155,7 +240,11 @@ def main():
             "edge_relaxations_per_s_trace_only": edges_per_step / (trace_ms * 1e-3),
             "shots_per_s": len(m.modes) * S / (wall / args.steps),
             "useful_edges_per_field": E, "solves_per_step": solves_per_step,
+            "trace_stats_last_step": st,
+            "raw_over_useful": {"tau": raw[0] / edges_per_step, "hop": raw[1] / edges_per_step},
+            "kernels": kernels,
         },
+        "roofline": roof,
     }
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(m, E, fields_per_step)

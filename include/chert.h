@@ -185,12 +185,27 @@ enum {
   CHERT_OUT_PRED_A = 16
 };
 
+/* Work counters of one trace call, per phase (0 = traveltimes, 1 = hop
+ * counts for the predecessors, 2 = t*). */
+typedef struct chert_trace_stats {
+  int32_t rounds[3];           /* relaxation rounds until no tile changed   */
+  int32_t reserved;
+  int64_t tile_visits[3];      /* (problem, tile) workgroup visits           */
+  int64_t edge_relaxations[3]; /* raw edges examined (pulls + pushes)        */
+  int64_t levels_sum[3];       /* push levels summed over visits             */
+  int32_t levels_max[3];       /* most push levels in one visit              */
+  int32_t reserved2;
+} chert_trace_stats;
+
 typedef struct chert_trace_opts {
   uint32_t outputs;   /* CHERT_OUT_* bits.  TSTAR needs TAU_R and PRED_P;
                          PRED_P needs TAU_R; PRED_A needs TAU_I.           */
   int32_t tile_x;     /* relaxation tile width in nodes (0 = default 32)   */
   int32_t tile_z;     /* relaxation tile height in nodes (0 = default 32)  */
   int32_t max_rounds; /* cap on relaxation rounds per phase (0 = default)  */
+  int32_t push_group; /* star offsets per push work item: 1, 2 or 4 (0 = 2) */
+  int32_t reserved;   /* must be 0                                          */
+  chert_trace_stats *stats_host; /* nullable: filled when the call returns */
 } chert_trace_opts;
 
 /* Scratch needed by chert_trace_field for these arguments. */
@@ -259,6 +274,19 @@ int chert_extract_raypath(const int32_t *pred_host, int64_t n_nodes,
  * arrays may be NULL to count only. */
 int chert_star_2d(int32_t radius, double hx, double hz, int32_t n_dirs,
                   int32_t *ox, int32_t *oz, double *len, int32_t *bin);
+
+/* Measurement support.  While enabled, every kernel launch the library
+ * makes (or, if `only` is non-NULL, every launch of the kernel of that name)
+ * is bracketed by HIP events on its stream; chert_prof_read() synchronises
+ * those events and returns per-kernel launch counts and summed durations.
+ * Enabling clears the totals.  Host, not thread-safe. */
+typedef struct chert_prof_entry {
+  char name[40];
+  int64_t launches;
+  double total_ms;
+} chert_prof_entry;
+int chert_prof_enable(int32_t on, const char *only);
+int chert_prof_read(chert_prof_entry *out, int32_t capacity, int32_t *n_out);
 
 const char *chert_last_error(void);
 

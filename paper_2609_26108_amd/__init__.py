@@ -34,6 +34,7 @@ EXPORTS = (
     "chert_trace_workspace_bytes", "chert_trace_field",
     "chert_trace_batch_workspace_bytes", "chert_trace_batch",
     "chert_extract_raypath", "chert_star_2d", "chert_last_error",
+    "chert_prof_enable", "chert_prof_read",
 )
 
 
@@ -80,9 +81,28 @@ class TraceJob(ctypes.Structure):
                 ("pred_a_dev", ctypes.c_void_p)]
 
 
+class TraceStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32),
+                ("tile_visits", ctypes.c_int64 * 3), ("edge_relaxations", ctypes.c_int64 * 3),
+                ("levels_sum", ctypes.c_int64 * 3), ("levels_max", ctypes.c_int32 * 3),
+                ("reserved2", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"rounds": list(self.rounds), "tile_visits": list(self.tile_visits),
+                "edge_relaxations": list(self.edge_relaxations),
+                "levels_sum": list(self.levels_sum), "levels_max": list(self.levels_max)}
+
+
 class TraceOpts(ctypes.Structure):
     _fields_ = [("outputs", ctypes.c_uint32), ("tile_x", ctypes.c_int32),
-                ("tile_z", ctypes.c_int32), ("max_rounds", ctypes.c_int32)]
+                ("tile_z", ctypes.c_int32), ("max_rounds", ctypes.c_int32),
+                ("push_group", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("stats_host", ctypes.c_void_p)]
+
+
+class ProfEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -116,6 +136,8 @@ def lib():
         L.chert_trace_batch.argtypes = [P, i32, P, P, sz, P]
         L.chert_extract_raypath.argtypes = [P, i64, i64, i64, P, i64, P]
         L.chert_star_2d.argtypes = [i32, d, d, i32, P, P, P, P]
+        L.chert_prof_enable.argtypes = [i32, ctypes.c_char_p]
+        L.chert_prof_read.argtypes = [P, i32, P]
         _lib = L
     return _lib
 
@@ -221,8 +243,25 @@ def make_grid(nx, nz, hx, hz, radius, class_id_dev):
     return g
 
 
-def trace_opts(outputs=OUT_ALL, tile_x=0, tile_z=0, max_rounds=0):
-    return TraceOpts(outputs, tile_x, tile_z, max_rounds)
+def trace_opts(outputs=OUT_ALL, tile_x=0, tile_z=0, max_rounds=0, stats=None, push_group=0):
+    """stats: a TraceStats to fill (kept referenced by the returned options)."""
+    o = TraceOpts(outputs, tile_x, tile_z, max_rounds, push_group, 0,
+                  ctypes.addressof(stats) if stats is not None else None)
+    o._stats = stats
+    return o
+
+
+def chert_prof_enable(on=True, only=None):
+    _check(lib().chert_prof_enable(1 if on else 0, only.encode() if only else None))
+
+
+def chert_prof_read():
+    """{kernel name: (launches, total_ms)} of the current profiling window."""
+    n = ctypes.c_int32(0)
+    _check(lib().chert_prof_read(None, 0, ctypes.byref(n)))
+    arr = (ProfEntry * max(n.value, 1))()
+    _check(lib().chert_prof_read(arr, n.value, ctypes.byref(n)))
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(n.value)}
 
 
 def chert_trace_workspace_bytes(desc, n_classes, grid, n_src, opts):

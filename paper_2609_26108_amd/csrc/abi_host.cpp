@@ -5,6 +5,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <string>
+#include <vector>
+
 #include "chert.h"
 #include "chert_internal.h"
 
@@ -50,9 +53,89 @@ int star_2d(int R, double hx, double hz, int n_dirs, int32_t* ox, int32_t* oz, d
   return n;
 }
 
+// ------------------------------------------------------------ profiling --
+
+struct ProfRec {
+  std::string name;
+  hipEvent_t start, stop;
+};
+static bool g_prof_on = false;
+static std::string g_prof_only;           // empty: every kernel
+static std::vector<ProfRec> g_prof;       // records of this profiling window
+static std::vector<hipEvent_t> g_pool;    // reusable events
+
+static hipEvent_t pool_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int prof_begin(const char* name, hipStream_t s) {
+  if (!g_prof_on) return -1;
+  if (!g_prof_only.empty() && g_prof_only != name) return -1;
+  ProfRec r;
+  r.name = name;
+  r.start = pool_event();
+  r.stop = pool_event();
+  if (!r.start || !r.stop) return -1;
+  hipEventRecord(r.start, s);
+  g_prof.push_back(r);
+  return (int)g_prof.size() - 1;
+}
+
+void prof_end(int slot, hipStream_t s) {
+  if (slot < 0 || slot >= (int)g_prof.size()) return;
+  hipEventRecord(g_prof[slot].stop, s);
+}
+
+static void prof_recycle() {
+  for (auto& r : g_prof) {
+    g_pool.push_back(r.start);
+    g_pool.push_back(r.stop);
+  }
+  g_prof.clear();
+}
+
 }  // namespace chert
 
 using namespace chert;
+
+extern "C" int chert_prof_enable(int32_t on, const char* only) {
+  if (on) prof_recycle();
+  g_prof_only = only ? only : "";
+  g_prof_on = on != 0;
+  return CHERT_OK;
+}
+
+extern "C" int chert_prof_read(chert_prof_entry* out, int32_t capacity, int32_t* n_out) {
+  if (!n_out) return fail(CHERT_ERR_INVALID_ARG, "null count");
+  std::vector<chert_prof_entry> acc;
+  for (auto& r : g_prof) {
+    hipError_t e = hipEventSynchronize(r.stop);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.start, r.stop);
+    if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+    size_t k = 0;
+    for (; k < acc.size(); ++k)
+      if (r.name == acc[k].name) break;
+    if (k == acc.size()) {
+      chert_prof_entry z{};
+      snprintf(z.name, sizeof(z.name), "%s", r.name.c_str());
+      acc.push_back(z);
+    }
+    acc[k].launches += 1;
+    acc[k].total_ms += ms;
+  }
+  *n_out = (int32_t)acc.size();
+  if (out)
+    for (int32_t i = 0; i < capacity && i < (int32_t)acc.size(); ++i) out[i] = acc[i];
+  return CHERT_OK;
+}
 
 extern "C" const char* chert_last_error(void) { return g_err; }
 

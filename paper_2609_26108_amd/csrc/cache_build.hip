@@ -356,13 +356,13 @@ extern "C" int chert_build_cache(const chert_cache_desc* d, const chert_class* c
   sa.n_sweep = d->n_sweep;
   sa.table = (double2*)workspace_dev;
 
-  hipLaunchKernelGGL(k_write_header, dim3(1), dim3(64), 0, s, cache, d->dim, d->n_dirs,
+  CHERT_LAUNCH("k_write_header", k_write_header, dim3(1), dim3(64), 0, s, cache, d->dim, d->n_dirs,
                      d->mode_mask, d->kernel, d->n_sweep, n_classes);
   if (sa.n_modes > 0) {
     int64_t total = (int64_t)sa.n_modes * n_classes * d->n_sweep;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_sweep, dim3((unsigned)blocks), dim3(256), 0, s, sa);
+    CHERT_LAUNCH("k_sweep", k_sweep, dim3((unsigned)blocks), dim3(256), 0, s, sa);
 
     SolveArgs so{};
     so.classes = classes_dev;
@@ -378,7 +378,7 @@ extern "C" int chert_build_cache(const chert_cache_desc* d, const chert_class* c
     int chunks = (d->n_dirs / 2 + 63) / 64;
     int64_t grid = (int64_t)sa.n_modes * n_classes * chunks;
     if (grid > 0x7fffffff) return fail(CHERT_ERR_INVALID_ARG, "too many classes");
-    hipLaunchKernelGGL(k_solve, dim3((unsigned)grid), dim3(64),
+    CHERT_LAUNCH("k_solve", k_solve, dim3((unsigned)grid), dim3(64),
                        (size_t)d->n_sweep * sizeof(double2), s, so);
   }
   hipError_t e = hipGetLastError();

@@ -1,6 +1,7 @@
 // Host-side helpers shared by the library's translation units.
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -23,4 +24,17 @@ int fail(int code, const char* msg);
 int star_2d(int R, double hx, double hz, int n_dirs, int32_t* ox, int32_t* oz, double* L,
             int32_t* bin);
 
+// Kernel timing for chert_prof_*: returns a slot (or -1 when profiling is
+// off) after recording a start event on the stream; prof_end records the stop.
+int prof_begin(const char* name, hipStream_t s);
+void prof_end(int slot, hipStream_t s);
+
 }  // namespace chert
+
+// Launch with optional event bracketing (see chert_prof_enable).
+#define CHERT_LAUNCH(NAME, KERN, GRID, BLOCK, LDS, STREAM, ...)      \
+  do {                                                               \
+    int chert_slot_ = ::chert::prof_begin(NAME, STREAM);             \
+    hipLaunchKernelGGL(KERN, GRID, BLOCK, LDS, STREAM, __VA_ARGS__); \
+    ::chert::prof_end(chert_slot_, STREAM);                          \
+  } while (0)

@@ -39,6 +39,16 @@ constexpr int kLocalIterCap = 4096;
 constexpr int32_t kHopUnset = 0x7fffffff;
 constexpr int kFieldR = 0, kFieldI = 1;
 constexpr size_t kWLdsBytes = 48 * 1024;  // class-pair table staged in LDS up to this
+// Tile flag bits.  Between two visits of a tile only its halo can change
+// (interior nodes are written by the owning tile alone, which leaves them
+// locally converged), so a visit pulls just the R-wide border band unless a
+// full pull is requested.
+constexpr int kFlagActive = 1;  // a neighbour changed nodes in our halo
+constexpr int kFlagFull = 2;    // pull every interior node (iteration cap hit)
+constexpr int kFlagSeed = 4;    // first visit of the source tile: push the source
+// LDS class ids of halo cells carry this bit (push targets must be interior)
+constexpr int32_t kHaloBit = 0x40000000;
+constexpr int32_t kClassMask = 0x3fffffff;
 
 struct JobDev {
   int nx, nz;     // nodes (nx * nz < 2^31)
@@ -71,8 +81,21 @@ struct RelaxArgs {
   int32_t* flags;    // [2][n_tiles]
   int32_t* counter;  // [max_rounds + 2]
   int32_t* err;      // out-of-range class ids seen
+  unsigned long long* stats;  // [3 phases][2]: tile visits, raw edges examined
   int w_lds_doubles; // LDS room for W
 };
+
+// one tile visit of a phase: count it, the edges it examined and its push
+// levels (stats layout: [phase][visits, edges], then levels sum, levels max)
+__device__ __forceinline__ void count_visit(const RelaxArgs& a, int phase, long long edges,
+                                            int levels) {
+  if (threadIdx.x == 0) {
+    atomicAdd(&a.stats[2 * phase], 1ull);
+    atomicAdd(&a.stats[2 * phase + 1], (unsigned long long)edges);
+    atomicAdd(&a.stats[6 + phase], (unsigned long long)levels);
+    atomicMax(&a.stats[9 + phase], (unsigned long long)levels);
+  }
+}
 
 // ------------------------------------------------------------- weights ---
 
@@ -107,10 +130,14 @@ __global__ void k_weights(double* W, int K, int n_off, const double* V, const do
 // ---------------------------------------------------------------- init ---
 
 // blockIdx.y = problem; x strides over its nodes
-__global__ void k_init_fields(const ProbDev* probs, const JobDev* jobs, int32_t* err) {
+__global__ void k_init_fields(const ProbDev* probs, const JobDev* jobs, int32_t* err,
+                              unsigned long long* stats) {
   const ProbDev pr = probs[blockIdx.y];
   const int64_t n = (int64_t)jobs[pr.job].nx * jobs[pr.job].nz;
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *err = 0;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 12) {
+    if (threadIdx.x == 0) *err = 0;
+    stats[threadIdx.x] = 0ull;
+  }
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * blockDim.x) {
     pr.tau[j] = (j == pr.src) ? 0.0 : INFINITY;
@@ -134,7 +161,7 @@ __global__ void k_seed_flags(int32_t* flags, int32_t* counter, const ProbDev* pr
   if (tstar_phase && pr.tstar == nullptr) return;
   const JobDev jb = jobs[pr.job];
   int sx = (int)(pr.src % jb.nx), sz = (int)(pr.src / jb.nx);
-  flags[pr.tile_base + (sz / tz) * jb.ntx + (sx / tx)] = 1;
+  flags[pr.tile_base + (sz / tz) * jb.ntx + (sx / tx)] = kFlagActive | kFlagSeed;
   atomicAdd(&counter[0], 1);
 }
 
@@ -144,13 +171,16 @@ struct TileCtx {
   int p, t, tx, tz;
   int x0, z0;    // first interior node
   int txe, tze;  // interior extent (ragged at the grid edge)
-  int active;
+  int active;    // flag bits (0 = not active this round)
 };
 
 // Claim this workgroup's (problem, tile) for the round: find the problem by
 // binary search over the tile bases, read and clear the tile's flag.
 __device__ __forceinline__ TileCtx tile_begin(const RelaxArgs& a, int round, int* s_flag,
                                               int* s_prob) {
+  // Plain round-robin order: the active tiles of a round form a compact
+  // wavefront band, and dealing consecutive tiles to different XCDs spreads
+  // that band over all of them (banding tiles per XCD measured slower).
   const int T = blockIdx.x;
   int32_t* fin = a.flags + (int64_t)(round & 1) * a.n_tiles;
   if (threadIdx.x == 0) {
@@ -208,14 +238,15 @@ __device__ __forceinline__ void activate(const RelaxArgs& a, int round, const Ti
     int nx_ = c.tx + dx, nz_ = c.tz + dz;
     if (nx_ < 0 || nx_ >= jb.ntx || nz_ < 0 || nz_ >= jb.ntz) continue;
     int32_t* f = &fout[pr.tile_base + nz_ * jb.ntx + nx_];
-    if (atomicOr(f, 1) == 0) atomicAdd(&a.counter[round + 1], 1);
+    const int32_t bits = (bit == 4) ? (kFlagActive | kFlagFull) : kFlagActive;
+    if (atomicOr(f, bits) == 0) atomicAdd(&a.counter[round + 1], 1);
   }
 }
 
 struct Smem {
   double* val;    // [lw*lh] field values
   int32_t* ival;  // [lw*lh] hop counts / predecessor offsets
-  int32_t* cls;   // [lw*lh] class ids: -1 outside the grid, -2 out of range
+  int32_t* cls;   // [lw*lh] class ids (| kHaloBit in the halo); -1 outside, -2 bad id
   int32_t* off;   // [n_off] LDS offsets of the star
   double* W;      // staged class-pair table
   int32_t* l0;    // frontier buffers (interior LDS indices)
@@ -263,6 +294,9 @@ __device__ __forceinline__ void load_common(const RelaxArgs& a, const TileCtx& c
       if (k < 0 || k >= jb.K) {
         atomicAdd(a.err, 1);
         k = -2;
+      } else {
+        const int lx = q % lw - R, lz = q / lw - R;
+        if (lx < 0 || lx >= c.txe || lz < 0 || lz >= c.tze) k |= kHaloBit;
       }
     }
     s.cls[q] = k;
@@ -293,13 +327,34 @@ __device__ __forceinline__ void frontier_add(bool flag, int node, int32_t* list,
   if (flag) list[base + __popcll(b & ((1ull << lane) - 1ull))] = node;
 }
 
-__device__ __forceinline__ bool interior(int l, int lw, int R, int txe, int tze) {
-  int x = l % lw - R, z = l / lw - R;
-  return x >= 0 && x < txe && z >= 0 && z < tze;
-}
 
 __device__ __forceinline__ unsigned long long dbits(double x) {
   return (unsigned long long)__double_as_longlong(x);
+}
+
+// Does this visit pull node ml (LDS index)?  Border band, or all on kFlagFull.
+__device__ __forceinline__ bool pulls(const RelaxArgs& a, const TileCtx& c, int ml) {
+  if (c.active & kFlagFull) return true;
+  const int x = ml % a.lw - a.R, z = ml / a.lw - a.R;
+  return x < a.R || x >= a.tx - a.R || z < a.R || z >= a.tz - a.R;
+}
+
+// Number of nodes pulls() selects in this tile (for the work counters).
+__device__ __forceinline__ long long pull_count(const RelaxArgs& a, const TileCtx& c) {
+  const long long all = (long long)c.txe * c.tze;
+  if (c.active & kFlagFull) return all;
+  const int ix = max(0, min(c.txe, a.tx - a.R) - a.R);
+  const int iz = max(0, min(c.tze, a.tz - a.R) - a.R);
+  return all - (long long)ix * iz;
+}
+
+// LDS index of the problem's source if this visit seeds it, else -1.
+__device__ __forceinline__ int seed_node(const RelaxArgs& a, const TileCtx& c, int64_t src,
+                                         int nx) {
+  if (!(c.active & kFlagSeed)) return -1;
+  const int sx = (int)(src % nx) - c.x0, sz = (int)(src / nx) - c.z0;
+  if (sx < 0 || sx >= c.txe || sz < 0 || sz >= c.tze) return -1;
+  return (sz + a.R) * a.lw + (sx + a.R);
 }
 
 // LDS index of this thread's interior node, or -1.
@@ -311,18 +366,14 @@ __device__ __forceinline__ int my_node(const RelaxArgs& a, const TileCtx& c) {
   return (z + a.R) * a.lw + (x + a.R);
 }
 
-// Loop bound shared by every thread (a multiple of the block size), so each
-// wavefront reaches every frontier_add together.
-__device__ __forceinline__ int uniform_bound(int total) {
-  return (total + kRelaxThreads - 1) / kRelaxThreads * kRelaxThreads;
-}
 
 // ----------------------------------------------------- relaxation phases ---
 
 // Phase TAU: tau_j <- min(tau_j, tau_i + w_ij) (eq 31).
+template <int G>
 __global__ void __launch_bounds__(kRelaxThreads) k_relax_tau(RelaxArgs a, int round) {
   extern __shared__ double smem_d[];
-  __shared__ int s_flag, s_prob, s_mask, s_cnt[2];
+  __shared__ int s_flag, s_prob, s_mask, s_cnt[3];
   const TileCtx c = tile_begin(a, round, &s_flag, &s_prob);
   if (!c.active) return;
   const Smem s = carve(a, smem_d);
@@ -334,6 +385,7 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_tau(RelaxArgs a, int ro
     s_mask = 0;
     s_cnt[0] = 0;
     s_cnt[1] = 0;
+    s_cnt[2] = 0;
   }
   load_common(a, c, jb, s);
   for (int q = threadIdx.x; q < n; q += blockDim.x) {
@@ -344,12 +396,13 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_tau(RelaxArgs a, int ro
   const double* Wp = stage_w(a, jb, pr.field, s);
   __syncthreads();
   const int ml = my_node(a, c);
+  long long raw = pull_count(a, c) * n_off;
   const double orig = ml >= 0 ? s.val[ml] : 0.0;
 
-  // pull once over every interior node
+  // pull over the border band (or every node), then seed the source
   {
     bool improved = false;
-    if (ml >= 0) {
+    if (ml >= 0 && pulls(a, c, ml)) {
       const int kj = s.cls[ml];
       if (kj >= 0) {
         const double cur = s.val[ml];
@@ -358,7 +411,8 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_tau(RelaxArgs a, int ro
           const int ii = ml - s.off[o];
           const int ki = s.cls[ii];
           if (ki < 0) continue;
-          const double cand = __dadd_rn(s.val[ii], Wp[(ki * K + kj) * n_off + o]);
+          const double cand =
+              __dadd_rn(s.val[ii], Wp[((ki & kClassMask) * K + kj) * n_off + o]);
           if (cand < best) best = cand;
         }
         if (best < cur) {
@@ -370,49 +424,69 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_tau(RelaxArgs a, int ro
     }
     frontier_add(improved, ml, s.l0, &s_cnt[0]);
   }
+  if (threadIdx.x == 0) {
+    const int sn = seed_node(a, c, pr.src, jb.nx);
+    if (sn >= 0 && s.cls[sn] >= 0 && atomicExch(&s.inq[sn], 1) != 1)
+      s.l0[atomicAdd(&s_cnt[0], 1)] = sn;
+  }
   __syncthreads();
 
-  // push iterations over the frontier
-  const int q_step = kRelaxThreads / n_off, r_step = kRelaxThreads % n_off;
-  int cur = 0, it = 0;
+  // push iterations over the frontier: one barrier per level; counters
+  // rotate over three slots, the dedupe stamp is the level number
+  int ci = 0, it = 1;
   int nf = s_cnt[0];
-  while (nf > 0 && it < kLocalIterCap) {
-    const int nxt = cur ^ 1;
-    int32_t* const lcur = cur ? s.l1 : s.l0;
-    int32_t* const lnxt = cur ? s.l0 : s.l1;
-    for (int f = threadIdx.x; f < nf; f += blockDim.x) s.inq[lcur[f]] = 0;
-    if (threadIdx.x == 0) s_cnt[nxt] = 0;
-    __syncthreads();
-    const int total = nf * n_off;
-    const int bound = uniform_bound(total);
-    int f = threadIdx.x / n_off, o = threadIdx.x % n_off;
+  const int ngroups = (n_off + G - 1) / G;
+  const int q_step = kRelaxThreads / ngroups, r_step = kRelaxThreads % ngroups;
+  while (nf > 0 && it <= kLocalIterCap) {
+    const int cn = ci == 2 ? 0 : ci + 1, cz = cn == 2 ? 0 : cn + 1;
+    int32_t* const lcur = (it & 1) ? s.l0 : s.l1;
+    int32_t* const lnxt = (it & 1) ? s.l1 : s.l0;
+    if (threadIdx.x == 0) s_cnt[cz] = 0;
+    raw += (long long)nf * n_off;
+    // work items = (frontier node, group of G offsets), spread over the block;
+    // every thread runs the same trip count so frontier_add sees whole waves
+    const int total = nf * ngroups;
+    const int bound = (total + kRelaxThreads - 1) / kRelaxThreads * kRelaxThreads;
+    int f = threadIdx.x / ngroups, g = threadIdx.x % ngroups;
     for (int item = threadIdx.x; item < bound; item += kRelaxThreads) {
-      bool improved = false;
-      int j = 0;
-      if (item < total) {
-        const int i = lcur[f];
-        j = i + s.off[o];
-        const int ki = s.cls[i], kj = s.cls[j];
-        if (kj >= 0 && interior(j, lw, R, c.txe, c.tze)) {
-          const double cand = __dadd_rn(s.val[i], Wp[(ki * K + kj) * n_off + o]);
-          const unsigned long long old =
-              atomicMin((unsigned long long*)&s.val[j], dbits(cand));
-          if (dbits(cand) < old) improved = atomicExch(&s.inq[j], 1) == 0;
+      const bool live = item < total;
+      const int i = live ? lcur[f] : 0;
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        bool improved = false;
+        int jj = 0;
+        const int o = g * G + u;
+        if (live && o < n_off) {
+          const double vi = s.val[i];
+          const double* Wi = Wp + (s.cls[i] & kClassMask) * K * n_off;
+            const int j = i + s.off[o];
+            const int kj = s.cls[j];
+            if (kj >= 0 && !(kj & kHaloBit)) {
+              const double cand = __dadd_rn(vi, Wi[kj * n_off + o]);
+              // plain read first: most pushes do not improve, skip their atomic
+              if (cand < s.val[j]) {
+                const unsigned long long old =
+                    atomicMin((unsigned long long*)&s.val[j], dbits(cand));
+                if (dbits(cand) < old) {
+                  improved = atomicExch(&s.inq[j], it + 1) != it + 1;
+                  jj = j;
+                }
+              }
+            }
         }
+        frontier_add(improved, jj, lnxt, &s_cnt[cn]);
       }
-      frontier_add(improved, j, lnxt, &s_cnt[nxt]);
       f += q_step;
-      o += r_step;
-      if (o >= n_off) {
-        o -= n_off;
+      g += r_step;
+      if (g >= ngroups) {
+        g -= ngroups;
         ++f;
       }
     }
     __syncthreads();
-    nf = s_cnt[nxt];
-    cur = nxt;
+    nf = s_cnt[cn];
+    ci = cn;
     ++it;
-    __syncthreads();
   }
 
   int mask = (nf > 0) ? (1 << 4) : 0;  // bit 4 = this tile again
@@ -421,15 +495,17 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_tau(RelaxArgs a, int ro
     pr.tau[(int64_t)(c.x0 + x) + (int64_t)jb.nx * (c.z0 + z)] = s.val[ml];
     mask |= border_bits(x, z, a.tx, a.tz, R);
   }
+  count_visit(a, 0, raw, it - 1);
   if (mask) atomicOr(&s_mask, mask);
   __syncthreads();
   if (threadIdx.x == 0 && s_mask) activate(a, round, c, pr, jb, s_mask);
 }
 
 // Phase HOP: BFS hop counts over tight edges, h_j <- min(h_j, h_i + 1).
+template <int G>
 __global__ void __launch_bounds__(kRelaxThreads) k_relax_hop(RelaxArgs a, int round) {
   extern __shared__ double smem_d[];
-  __shared__ int s_flag, s_prob, s_mask, s_cnt[2];
+  __shared__ int s_flag, s_prob, s_mask, s_cnt[3];
   const TileCtx c = tile_begin(a, round, &s_flag, &s_prob);
   if (!c.active) return;
   const Smem s = carve(a, smem_d);
@@ -441,6 +517,7 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_hop(RelaxArgs a, int ro
     s_mask = 0;
     s_cnt[0] = 0;
     s_cnt[1] = 0;
+    s_cnt[2] = 0;
   }
   load_common(a, c, jb, s);
   for (int q = threadIdx.x; q < n; q += blockDim.x) {
@@ -453,11 +530,12 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_hop(RelaxArgs a, int ro
   const double* Wp = stage_w(a, jb, pr.field, s);
   __syncthreads();
   const int ml = my_node(a, c);
+  long long raw = pull_count(a, c) * n_off;
   const int32_t orig = ml >= 0 ? s.ival[ml] : 0;
 
   {
     bool improved = false;
-    if (ml >= 0) {
+    if (ml >= 0 && pulls(a, c, ml)) {
       const int kj = s.cls[ml];
       const double tj = s.val[ml];
       if (kj >= 0 && tj < INFINITY) {
@@ -468,7 +546,8 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_hop(RelaxArgs a, int ro
           const int ki = s.cls[ii];
           const int32_t hi = s.ival[ii];
           if (ki < 0 || hi == kHopUnset || hi + 1 >= best) continue;
-          if (__dadd_rn(s.val[ii], Wp[(ki * K + kj) * n_off + o]) == tj) best = hi + 1;
+          if (__dadd_rn(s.val[ii], Wp[((ki & kClassMask) * K + kj) * n_off + o]) == tj)
+            best = hi + 1;
         }
         if (best < cur) {
           s.ival[ml] = best;
@@ -479,50 +558,68 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_hop(RelaxArgs a, int ro
     }
     frontier_add(improved, ml, s.l0, &s_cnt[0]);
   }
+  if (threadIdx.x == 0) {
+    const int sn = seed_node(a, c, pr.src, jb.nx);
+    if (sn >= 0 && s.cls[sn] >= 0 && atomicExch(&s.inq[sn], 1) != 1)
+      s.l0[atomicAdd(&s_cnt[0], 1)] = sn;
+  }
   __syncthreads();
 
-  const int q_step = kRelaxThreads / n_off, r_step = kRelaxThreads % n_off;
-  int cur = 0, it = 0;
+  int ci = 0, it = 1;
   int nf = s_cnt[0];
-  while (nf > 0 && it < kLocalIterCap) {
-    const int nxt = cur ^ 1;
-    int32_t* const lcur = cur ? s.l1 : s.l0;
-    int32_t* const lnxt = cur ? s.l0 : s.l1;
-    for (int f = threadIdx.x; f < nf; f += blockDim.x) s.inq[lcur[f]] = 0;
-    if (threadIdx.x == 0) s_cnt[nxt] = 0;
-    __syncthreads();
-    const int total = nf * n_off;
-    const int bound = uniform_bound(total);
-    int f = threadIdx.x / n_off, o = threadIdx.x % n_off;
+  const int ngroups = (n_off + G - 1) / G;
+  const int q_step = kRelaxThreads / ngroups, r_step = kRelaxThreads % ngroups;
+  while (nf > 0 && it <= kLocalIterCap) {
+    const int cn = ci == 2 ? 0 : ci + 1, cz = cn == 2 ? 0 : cn + 1;
+    int32_t* const lcur = (it & 1) ? s.l0 : s.l1;
+    int32_t* const lnxt = (it & 1) ? s.l1 : s.l0;
+    if (threadIdx.x == 0) s_cnt[cz] = 0;
+    raw += (long long)nf * n_off;
+    // work items = (frontier node, group of G offsets), spread over the block;
+    // every thread runs the same trip count so frontier_add sees whole waves
+    const int total = nf * ngroups;
+    const int bound = (total + kRelaxThreads - 1) / kRelaxThreads * kRelaxThreads;
+    int f = threadIdx.x / ngroups, g = threadIdx.x % ngroups;
     for (int item = threadIdx.x; item < bound; item += kRelaxThreads) {
-      bool improved = false;
-      int j = 0;
-      if (item < total) {
-        const int i = lcur[f];
-        j = i + s.off[o];
-        const int ki = s.cls[i], kj = s.cls[j];
-        if (kj >= 0 && interior(j, lw, R, c.txe, c.tze)) {
+      const bool live = item < total;
+      const int i = live ? lcur[f] : 0;
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        bool improved = false;
+        int jj = 0;
+        const int o = g * G + u;
+        if (live && o < n_off) {
+          const double vi = s.val[i];
           const int32_t cand = s.ival[i] + 1;
-          if (cand < s.ival[j] &&
-              __dadd_rn(s.val[i], Wp[(ki * K + kj) * n_off + o]) == s.val[j]) {
-            const int32_t old = atomicMin(&s.ival[j], cand);
-            if (cand < old) improved = atomicExch(&s.inq[j], 1) == 0;
-          }
+          const double* Wi = Wp + (s.cls[i] & kClassMask) * K * n_off;
+            const int j = i + s.off[o];
+            const int kj = s.cls[j];
+            if (kj >= 0 && !(kj & kHaloBit)) {
+              const double tj = s.val[j];
+              // tight edge into a reachable node (inf + w == inf is no edge)
+              if (cand < s.ival[j] && tj < INFINITY &&
+                  __dadd_rn(vi, Wi[kj * n_off + o]) == tj) {
+                const int32_t old = atomicMin(&s.ival[j], cand);
+                if (cand < old) {
+                  improved = atomicExch(&s.inq[j], it + 1) != it + 1;
+                  jj = j;
+                }
+              }
+            }
         }
+        frontier_add(improved, jj, lnxt, &s_cnt[cn]);
       }
-      frontier_add(improved, j, lnxt, &s_cnt[nxt]);
       f += q_step;
-      o += r_step;
-      if (o >= n_off) {
-        o -= n_off;
+      g += r_step;
+      if (g >= ngroups) {
+        g -= ngroups;
         ++f;
       }
     }
     __syncthreads();
-    nf = s_cnt[nxt];
-    cur = nxt;
+    nf = s_cnt[cn];
+    ci = cn;
     ++it;
-    __syncthreads();
   }
 
   int mask = (nf > 0) ? (1 << 4) : 0;
@@ -531,6 +628,7 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_hop(RelaxArgs a, int ro
     pr.hop[(int64_t)(c.x0 + x) + (int64_t)jb.nx * (c.z0 + z)] = s.ival[ml];
     mask |= border_bits(x, z, a.tx, a.tz, R);
   }
+  count_visit(a, 1, raw, it - 1);
   if (mask) atomicOr(&s_mask, mask);
   __syncthreads();
   if (threadIdx.x == 0 && s_mask) activate(a, round, c, pr, jb, s_mask);
@@ -594,9 +692,10 @@ __global__ void k_pred_offsets(RelaxArgs a) {
 // Phase TSTAR: t*_j = t*_pred + w_I(pred -> j) once t*_pred is known; a
 // node whose value became known pushes to the children naming it as their
 // predecessor.
+template <int G>
 __global__ void __launch_bounds__(kRelaxThreads) k_relax_tstar(RelaxArgs a, int round) {
   extern __shared__ double smem_d[];
-  __shared__ int s_flag, s_prob, s_mask, s_cnt[2];
+  __shared__ int s_flag, s_prob, s_mask, s_cnt[3];
   const TileCtx c = tile_begin(a, round, &s_flag, &s_prob);
   if (!c.active) return;
   const Smem s = carve(a, smem_d);
@@ -609,6 +708,7 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_tstar(RelaxArgs a, int 
     s_mask = 0;
     s_cnt[0] = 0;
     s_cnt[1] = 0;
+    s_cnt[2] = 0;
   }
   load_common(a, c, jb, s);
   for (int q = threadIdx.x; q < n; q += blockDim.x) {
@@ -623,63 +723,79 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_tstar(RelaxArgs a, int 
   const double* WI = stage_w(a, jb, kFieldI, s);
   __syncthreads();
   const int ml = my_node(a, c);
+  long long raw = pull_count(a, c);
 
   {
     bool known = false;
-    if (ml >= 0) {
+    if (ml >= 0 && pulls(a, c, ml)) {
       const int o = s.ival[ml];
       if (o >= 0 && isnan(s.val[ml])) {
         const int ii = ml - s.off[o];
         const double tp = s.val[ii];
         if (!isnan(tp)) {
-          s.val[ml] = __dadd_rn(tp, WI[(s.cls[ii] * K + s.cls[ml]) * n_off + o]);
+          s.val[ml] = __dadd_rn(tp, WI[((s.cls[ii] & kClassMask) * K + s.cls[ml]) * n_off + o]);
           known = true;
         }
       }
     }
     frontier_add(known, ml, s.l0, &s_cnt[0]);
   }
+  if (threadIdx.x == 0) {
+    const int sn = seed_node(a, c, pr.src, jb.nx);
+    if (sn >= 0 && s.cls[sn] >= 0 && atomicExch(&s.inq[sn], 1) != 1)
+      s.l0[atomicAdd(&s_cnt[0], 1)] = sn;
+  }
   __syncthreads();
 
-  const int q_step = kRelaxThreads / n_off, r_step = kRelaxThreads % n_off;
-  int cur = 0, it = 0;
+  int ci = 0, it = 1;
   int nf = s_cnt[0];
-  while (nf > 0 && it < kLocalIterCap) {
-    const int nxt = cur ^ 1;
-    int32_t* const lcur = cur ? s.l1 : s.l0;
-    int32_t* const lnxt = cur ? s.l0 : s.l1;
-    if (threadIdx.x == 0) s_cnt[nxt] = 0;
-    __syncthreads();
-    const int total = nf * n_off;
-    const int bound = uniform_bound(total);
-    int f = threadIdx.x / n_off, o = threadIdx.x % n_off;
+  const int ngroups = (n_off + G - 1) / G;
+  const int q_step = kRelaxThreads / ngroups, r_step = kRelaxThreads % ngroups;
+  while (nf > 0 && it <= kLocalIterCap) {
+    const int cn = ci == 2 ? 0 : ci + 1, cz = cn == 2 ? 0 : cn + 1;
+    int32_t* const lcur = (it & 1) ? s.l0 : s.l1;
+    int32_t* const lnxt = (it & 1) ? s.l1 : s.l0;
+    if (threadIdx.x == 0) s_cnt[cz] = 0;
+    raw += (long long)nf * n_off;
+    // work items = (frontier node, group of G offsets), spread over the block;
+    // every thread runs the same trip count so frontier_add sees whole waves
+    const int total = nf * ngroups;
+    const int bound = (total + kRelaxThreads - 1) / kRelaxThreads * kRelaxThreads;
+    int f = threadIdx.x / ngroups, g = threadIdx.x % ngroups;
     for (int item = threadIdx.x; item < bound; item += kRelaxThreads) {
-      bool known = false;
-      int j = 0;
-      if (item < total) {
-        const int i = lcur[f];
-        j = i + s.off[o];
-        // j's predecessor is i (j - i = o; j interior).  One parent per
-        // child, so one writer; the NaN test skips children the pull already
-        // resolved, keeping every node in at most one frontier.
-        if (s.ival[j] == o && isnan(s.val[j])) {
-          s.val[j] = __dadd_rn(s.val[i], WI[(s.cls[i] * K + s.cls[j]) * n_off + o]);
-          known = true;
+      const bool live = item < total;
+      const int i = live ? lcur[f] : 0;
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        bool improved = false;
+        int jj = 0;
+        const int o = g * G + u;
+        if (live && o < n_off) {
+          const double vi = s.val[i];
+          const double* Wi = WI + (s.cls[i] & kClassMask) * K * n_off;
+            const int j = i + s.off[o];
+            // j's predecessor is i (j - i = o; only interior nodes carry one).
+            // One parent per child, so one writer; the NaN test skips
+            // children the pull already resolved.
+            if (s.ival[j] == o && isnan(s.val[j])) {
+              s.val[j] = __dadd_rn(vi, Wi[(s.cls[j] & kClassMask) * n_off + o]);
+              improved = true;
+              jj = j;
+            }
         }
+        frontier_add(improved, jj, lnxt, &s_cnt[cn]);
       }
-      frontier_add(known, j, lnxt, &s_cnt[nxt]);
       f += q_step;
-      o += r_step;
-      if (o >= n_off) {
-        o -= n_off;
+      g += r_step;
+      if (g >= ngroups) {
+        g -= ngroups;
         ++f;
       }
     }
     __syncthreads();
-    nf = s_cnt[nxt];
-    cur = nxt;
+    nf = s_cnt[cn];
+    ci = cn;
     ++it;
-    __syncthreads();
   }
 
   int mask = (nf > 0) ? (1 << 4) : 0;
@@ -691,6 +807,7 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_tstar(RelaxArgs a, int 
       mask |= border_bits(x, z, a.tx, a.tz, R);
     }
   }
+  count_visit(a, 2, raw, it - 1);
   if (mask) atomicOr(&s_mask, mask);
   __syncthreads();
   if (threadIdx.x == 0 && s_mask) activate(a, round, c, pr, jb, s_mask);
@@ -770,6 +887,9 @@ static int validate_job(const chert_trace_job& j, uint32_t outs) {
 
 static int validate_opts(const chert_trace_opts* o) {
   if (!o) return fail(CHERT_ERR_INVALID_ARG, "null options");
+  if (o->push_group != 0 && o->push_group != 1 && o->push_group != 2 && o->push_group != 4)
+    return fail(CHERT_ERR_INVALID_ARG, "push_group must be 0, 1, 2 or 4");
+  if (o->reserved != 0) return fail(CHERT_ERR_INVALID_ARG, "reserved must be 0");
   uint32_t outs = o->outputs;
   if (outs == 0 || (outs & ~31u)) return fail(CHERT_ERR_INVALID_ARG, "bad output mask");
   if ((outs & CHERT_OUT_TSTAR) && !((outs & CHERT_OUT_TAU_R) && (outs & CHERT_OUT_PRED_P)))
@@ -847,21 +967,25 @@ static int make_plan(const chert_trace_job* jobs, int n_jobs, const chert_trace_
 }
 
 static int run_rounds(hipStream_t s, const RelaxArgs& a, void (*kern)(RelaxArgs, int),
-                      size_t lds, int max_rounds) {
+                      const char* name, size_t lds, int max_rounds, int* rounds) {
   const int batch = 8;
   int32_t counts[batch];
   for (int r = 0; r < max_rounds; r += batch) {
     int nb = batch;
     if (r + nb > max_rounds) nb = max_rounds - r;
     for (int q = 0; q < nb; ++q)
-      hipLaunchKernelGGL(kern, dim3((unsigned)a.n_tiles), dim3(kRelaxThreads), lds, s, a, r + q);
+      CHERT_LAUNCH(name, kern, dim3((unsigned)a.n_tiles), dim3(kRelaxThreads), lds, s, a, r + q);
     hipError_t e = hipMemcpyAsync(counts, a.counter + r + 1, sizeof(int32_t) * nb,
                                   hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
     for (int q = 0; q < nb; ++q)
-      if (counts[q] == 0) return CHERT_OK;
+      if (counts[q] == 0) {
+        *rounds = r + q + 1;
+        return CHERT_OK;
+      }
   }
+  *rounds = max_rounds;
   return fail(CHERT_ERR_NO_CONVERGENCE, "relaxation round cap reached");
 }
 
@@ -969,6 +1093,7 @@ static int trace_batch(const chert_trace_job* jobs, int n_jobs, const chert_trac
   a.flags = (int32_t*)(ws + P.off_flags);
   a.counter = (int32_t*)(ws + P.off_counter);
   a.err = (int32_t*)(ws + P.off_err);
+  a.stats = (unsigned long long*)(ws + P.off_err + 64);
   a.w_lds_doubles = P.w_lds_doubles;
   const size_t lds = lds_bytes(P.lw, P.lh, P.w_lds_doubles, P.n_off, P.tx, P.tz);
 
@@ -986,7 +1111,7 @@ static int trace_batch(const chert_trace_job* jobs, int n_jobs, const chert_trac
     const int32_t* Sm = (const int32_t*)(cache + lay.status_offset) + mslice;
     int64_t tw = 2 * K * K * P.n_off;
     int64_t blocks = (tw + 255) / 256;
-    hipLaunchKernelGGL(k_weights, dim3((unsigned)(blocks > 65536 ? 65536 : blocks)), dim3(256),
+    CHERT_LAUNCH("k_weights", k_weights, dim3((unsigned)(blocks > 65536 ? 65536 : blocks)), dim3(256),
                        0, s, (double*)(ws + P.off_W[j]), (int)K, P.n_off, Vm, Am, Sm,
                        J.d->n_dirs, dL + (size_t)j * kMaxOffsets, dbin + (size_t)j * kMaxOffsets);
   }
@@ -994,34 +1119,55 @@ static int trace_batch(const chert_trace_job* jobs, int n_jobs, const chert_trac
   for (int64_t n : P.nodes) max_nodes = n > max_nodes ? n : max_nodes;
   const unsigned gx = (unsigned)((max_nodes + 255) / 256 > 1024 ? 1024 : (max_nodes + 255) / 256);
   const dim3 pgrid(gx, (unsigned)P.n_prob);
-  hipLaunchKernelGGL(k_init_fields, pgrid, dim3(256), 0, s, dprobs, djobs, a.err);
+  CHERT_LAUNCH("k_init_fields", k_init_fields, pgrid, dim3(256), 0, s, dprobs, djobs, a.err, a.stats);
   const int64_t n_flags = 2 * P.n_tiles;
   auto init_flags = [&](int tstar_phase) {
-    hipLaunchKernelGGL(k_clear_flags, dim3(256), dim3(256), 0, s, a.flags, n_flags, a.counter,
+    CHERT_LAUNCH("k_clear_flags", k_clear_flags, dim3(256), dim3(256), 0, s, a.flags, n_flags, a.counter,
                        P.max_rounds + 2);
-    hipLaunchKernelGGL(k_seed_flags, dim3((P.n_prob + 63) / 64), dim3(64), 0, s, a.flags,
+    CHERT_LAUNCH("k_seed_flags", k_seed_flags, dim3((P.n_prob + 63) / 64), dim3(64), 0, s, a.flags,
                        a.counter, dprobs, djobs, P.n_prob, P.tx, P.tz, tstar_phase);
   };
+  // push work-item grouping (template instance)
+  typedef void (*Kern)(RelaxArgs, int);
+  const int G = o->push_group ? o->push_group : 2;
+  Kern ktau = G == 1 ? k_relax_tau<1> : (G == 2 ? k_relax_tau<2> : k_relax_tau<4>);
+  Kern khop = G == 1 ? k_relax_hop<1> : (G == 2 ? k_relax_hop<2> : k_relax_hop<4>);
+  Kern ktst = G == 1 ? k_relax_tstar<1> : (G == 2 ? k_relax_tstar<2> : k_relax_tstar<4>);
+  int rounds[3] = {0, 0, 0};
   init_flags(0);
-  rc = run_rounds(s, a, k_relax_tau, lds, P.max_rounds);
+  rc = run_rounds(s, a, ktau, "k_relax_tau", lds, P.max_rounds, &rounds[0]);
   if (rc) return rc;
   if (outs & (CHERT_OUT_PRED_P | CHERT_OUT_PRED_A)) {
     init_flags(0);
-    rc = run_rounds(s, a, k_relax_hop, lds, P.max_rounds);
+    rc = run_rounds(s, a, khop, "k_relax_hop", lds, P.max_rounds, &rounds[1]);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_pred, pgrid, dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_pred_offsets, pgrid, dim3(256), 0, s, a);
+    CHERT_LAUNCH("k_pred", k_pred, pgrid, dim3(256), 0, s, a);
+    CHERT_LAUNCH("k_pred_offsets", k_pred_offsets, pgrid, dim3(256), 0, s, a);
   }
   if (outs & CHERT_OUT_TSTAR) {
     init_flags(1);
-    rc = run_rounds(s, a, k_relax_tstar, lds, P.max_rounds);
+    rc = run_rounds(s, a, ktst, "k_relax_tstar", lds, P.max_rounds, &rounds[2]);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_tstar_finish, pgrid, dim3(256), 0, s, dprobs, djobs);
+    CHERT_LAUNCH("k_tstar_finish", k_tstar_finish, pgrid, dim3(256), 0, s, dprobs, djobs);
   }
   int32_t herr = 0;
+  unsigned long long hstats[12];
   e = hipMemcpyAsync(&herr, a.err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hstats, a.stats, sizeof(hstats), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+  if (o->stats_host) {
+    chert_trace_stats* st = o->stats_host;
+    for (int ph = 0; ph < 3; ++ph) {
+      st->rounds[ph] = rounds[ph];
+      st->tile_visits[ph] = (int64_t)hstats[2 * ph];
+      st->edge_relaxations[ph] = (int64_t)hstats[2 * ph + 1];
+      st->levels_sum[ph] = (int64_t)hstats[6 + ph];
+      st->levels_max[ph] = (int32_t)hstats[9 + ph];
+    }
+    st->reserved = 0;
+  }
   if (herr) return fail(CHERT_ERR_INVALID_ARG, "class id out of range");
   return CHERT_OK;
 }
