@@ -88,6 +88,14 @@ int chert_class_from_thomsen(double vp0, double vs0, double rho, double eps,
                              double azimuth, double qp, double qs,
                              chert_class *out);
 
+/* Device batch of chert_class_from_thomsen for per-node media (one class per
+ * node).  params_dev: [n][10] doubles (vp0, vs0, rho, eps, delta, gamma,
+ * tilt, azimuth, qp, qs); out_dev: [n] classes.  A row the host function
+ * would reject becomes a class with NaN moduli, whose cache entries get
+ * CHERT_ST_NONPHYS.  Asynchronous on `stream`. */
+int chert_classes_from_thomsen(const double *params_dev, int64_t n,
+                               chert_class *out_dev, void *stream);
+
 /* ------------------------------------------------------------------------
  * Stage 1: the directional cache (eq 26; Algorithm 2, cache construction).
  * Entry (m, k, d) holds the homogeneous solution (eq 9) whose ray direction
@@ -104,7 +112,12 @@ typedef struct chert_cache_desc {
   uint32_t mode_mask; /* bit (1 << chert_mode) per mode to build            */
   int32_t kernel;     /* chert_kernel                                       */
   int32_t n_sweep;    /* theta_R sweep samples, >= 16 (1440 = 0.25 degree)  */
-  int32_t reserved;   /* must be 0                                          */
+  int32_t n_subset;   /* 0: every direction; else the number of columns     */
+  const int32_t *subset_host; /* n_subset direction indices, ascending,
+                         closed under d -> d + n_dirs/2 (mod n_dirs), at
+                         most 512; only these columns are stored and built
+                         (per-node caches need only the star's bins).  Read
+                         during the call only.                              */
 } chert_cache_desc;
 
 /* Field order of the cache arrays. */
@@ -120,12 +133,13 @@ enum {
   CHERT_NF = 8
 };
 
-/* Device layout of a cache blob (all offsets in bytes from its start):
+/* Device layout of a cache blob (all offsets in bytes from its start), with
+ * n_cols = n_subset if a subset is given, else n_dirs:
  *   [0, 256)            header: uint32 magic 'CHRT' (0x54524843), uint32
  *                       version (1), int32 dim, n_dirs, mode_mask, kernel,
- *                       n_sweep, reserved, int64 n_classes; rest zero.
- *   fields_offset       double fields[CHERT_NF][3][n_classes][n_dirs]
- *   status_offset       int32 status[3][n_classes][n_dirs]
+ *                       n_sweep, n_subset, int64 n_classes; rest zero.
+ *   fields_offset       double fields[CHERT_NF][3][n_classes][n_cols]
+ *   status_offset       int32 status[3][n_classes][n_cols]
  * Slots of modes outside mode_mask are left as they were.  The blob is
  * position-independent, so it may be copied to disk and back. */
 typedef struct chert_cache_layout {

@@ -57,6 +57,9 @@ def lib():
         L.orc_solve.argtypes = [P, i, i, i, d, P]
         L.orc_sweep.argtypes = [P, i, i, i, P, P, P, P]
         L.orc_build_cache_2d.argtypes = [P, l, i, u, i, i, P, P]
+        L.orc_build_cache_2d_cols.argtypes = [P, l, i, P, i, u, i, i, P, P]
+        L.orc_trace_2d_cols.argtypes = [l, l, d, d, P, i, i, P, i, P, P, P, l,
+                                        P, P, P, P, P, P, P]
         L.orc_star_2d.argtypes = [i, d, d, i, P, P, P, P]
         L.orc_trace_2d.argtypes = [l, l, d, d, P, i, i, P, P, P, l,
                                    P, P, P, P, P, P, P]
@@ -134,17 +137,26 @@ def sweep(cls, mode, reading=MEV, n_sweep=N_SWEEP):
 
 
 def build_cache_2d(classes, n_dirs=360, mode_mask=0b111, reading=MEV,
-                   n_sweep=N_SWEEP):
-    """Returns (fields [NF][3][K][n_dirs], status [3][K][n_dirs])."""
+                   n_sweep=N_SWEEP, subset=None):
+    """Returns (fields [NF][3][K][n_cols], status [3][K][n_cols]); subset =
+    ascending directions closed under reversal (None: all n_dirs)."""
     classes = np.ascontiguousarray(np.atleast_2d(classes), dtype=np.float64)
     K = classes.shape[0]
-    fields = np.full((NF, 3, K, n_dirs), np.nan)
-    status = np.zeros((3, K, n_dirs), dtype=np.int32)
-    rc = lib().orc_build_cache_2d(_p(classes), K, n_dirs, mode_mask, reading,
-                                  n_sweep, _p(fields), _p(status))
+    sub = None if subset is None else np.ascontiguousarray(subset, dtype=np.int32)
+    n_cols = n_dirs if sub is None else sub.size
+    fields = np.full((NF, 3, K, n_cols), np.nan)
+    status = np.zeros((3, K, n_cols), dtype=np.int32)
+    rc = lib().orc_build_cache_2d_cols(_p(classes), K, n_dirs, _p(sub),
+                                       0 if sub is None else sub.size, mode_mask,
+                                       reading, n_sweep, _p(fields), _p(status))
     if rc:
         raise ValueError(f"orc_build_cache_2d failed rc={rc}")
     return fields, status
+
+
+def star_subset(R, hx, hz, n_dirs=360):
+    """Sorted unique bins of the forward star (closed under reversal)."""
+    return np.unique(star_2d(R, hx, hz, n_dirs)[3]).astype(np.int32)
 
 
 # ------------------------------------------------------------------ graph --
@@ -159,22 +171,26 @@ def star_2d(R, hx, hz, n_dirs=360):
     return ox, oz, L, b
 
 
-def trace_2d(nx, nz, hx, hz, class_id, R, V, A, status, src, n_dirs=360):
-    """Dijkstra traveltimes for one mode from a class cache slice
-    V/A/status [K][n_dirs].  Returns dict of tauR, tauI, predP, predA,
-    tstar, hopP, hopA."""
+def trace_2d(nx, nz, hx, hz, class_id, R, V, A, status, src, n_dirs=360, subset=None):
+    """Dijkstra traveltimes for one mode from a cache slice V/A/status
+    [K][n_cols].  class_id None: one class per node.  Returns dict of tauR,
+    tauI, predP, predA, tstar, hopP, hopA."""
     n = nx * nz
-    cid = np.ascontiguousarray(class_id, dtype=np.int32).reshape(-1)
-    assert cid.size == n
+    cid = None
+    if class_id is not None:
+        cid = np.ascontiguousarray(class_id, dtype=np.int32).reshape(-1)
+        assert cid.size == n
+    sub = None if subset is None else np.ascontiguousarray(subset, dtype=np.int32)
     V = np.ascontiguousarray(V, dtype=np.float64)
     A = np.ascontiguousarray(A, dtype=np.float64)
     st = np.ascontiguousarray(status, dtype=np.int32)
     out = {k: np.zeros(n) for k in ("tauR", "tauI", "tstar")}
     out.update({k: np.zeros(n, np.int32) for k in ("predP", "predA", "hopP", "hopA")})
-    rc = lib().orc_trace_2d(nx, nz, hx, hz, _p(cid), R, n_dirs, _p(V), _p(A),
-                            _p(st), int(src), _p(out["tauR"]), _p(out["tauI"]),
-                            _p(out["predP"]), _p(out["predA"]), _p(out["tstar"]),
-                            _p(out["hopP"]), _p(out["hopA"]))
+    rc = lib().orc_trace_2d_cols(nx, nz, hx, hz, _p(cid), R, n_dirs, _p(sub),
+                                 0 if sub is None else sub.size, _p(V), _p(A),
+                                 _p(st), int(src), _p(out["tauR"]), _p(out["tauI"]),
+                                 _p(out["predP"]), _p(out["predA"]), _p(out["tstar"]),
+                                 _p(out["hopP"]), _p(out["hopA"]))
     if rc:
         raise ValueError(f"orc_trace_2d failed rc={rc}")
     return out

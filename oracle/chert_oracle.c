@@ -524,64 +524,84 @@ int orc_sweep(const double *cls, int mode, int reading, int n_sweep,
 /* O-7  the directional cache C(m, k, theta) (eq 26)                        */
 /* ------------------------------------------------------------------------ */
 
-/* fields: [ORC_NF][3 modes][n_classes][n_dirs]; status: [3][n_classes][n_dirs].
- * Modes outside mode_mask are left untouched. */
-int orc_build_cache_2d(const double *classes, long n_classes, int n_dirs,
-                       unsigned mode_mask, int reading, int n_sweep,
-                       double *fields, int32_t *status) {
+/* fields: [ORC_NF][3 modes][n_classes][n_cols]; status: [3][n_classes][n_cols].
+ * subset (ascending directions, closed under d -> d + n_dirs/2) selects the
+ * stored columns; NULL means every direction (n_cols = n_dirs).  Modes
+ * outside mode_mask are left untouched. */
+int orc_build_cache_2d_cols(const double *classes, long n_classes, int n_dirs,
+                            const int32_t *subset, int n_subset,
+                            unsigned mode_mask, int reading, int n_sweep,
+                            double *fields, int32_t *status) {
   if (n_dirs <= 0 || (n_dirs & 1) || n_sweep < 8) return 1;
-  long stride = 3L * n_classes * n_dirs;
-  sample_t *tab = (sample_t *)malloc(sizeof(sample_t) * (size_t)n_sweep);
-  if (!tab) return 2;
+  int n_cols = subset ? n_subset : n_dirs;
   int half = n_dirs / 2;
+  /* columns of each direction (-1: not stored) */
+  int *col = (int *)malloc(sizeof(int) * (size_t)n_dirs);
+  if (!col) return 2;
+  for (int d = 0; d < n_dirs; ++d) col[d] = subset ? -1 : d;
+  if (subset)
+    for (int q = 0; q < n_subset; ++q) col[subset[q]] = q;
+  for (int d = 0; d < half; ++d)
+    if ((col[d] < 0) != (col[d + half] < 0)) { free(col); return 3; }
+  long stride = 3L * n_classes * n_cols;
+  sample_t *tab = (sample_t *)malloc(sizeof(sample_t) * (size_t)n_sweep);
+  if (!tab) { free(col); return 2; }
   for (int mode = 0; mode < 3; ++mode) {
     if (!(mode_mask & (1u << mode))) continue;
     for (long k = 0; k < n_classes; ++k) {
       const double *cls = classes + 13 * k;
       medium_t m;
       load_medium(cls, &m);
-      long base = ((long)mode * n_classes + k) * n_dirs;
+      long base = ((long)mode * n_classes + k) * n_cols;
       int fluid = (mode != ORC_QP) && (cls[3] == 0.0 || (mode == ORC_QSH && cls[4] == 0.0));
       if (fluid) {
-        for (int d = 0; d < n_dirs; ++d) {
-          write_invalid(fields, stride, base + d);
-          status[base + d] = ORC_ST_FLUID;
+        for (int c = 0; c < n_cols; ++c) {
+          write_invalid(fields, stride, base + c);
+          status[base + c] = ORC_ST_FLUID;
         }
         continue;
       }
       sweep(&m, mode, reading, n_sweep, tab);
       for (int d = 0; d < half; ++d) {
+        if (col[d] < 0) continue;
+        long e0 = base + col[d], e1 = base + col[d + half];
         double psi_global = d * (2.0 * ORC_PI / n_dirs);
         double psi_star = wrap_pi(psi_global - m.tilt);
         entry_t e;
         int st = solve_direction(&m, mode, reading, n_sweep, tab, psi_star, &e);
         if (st & ORC_ST_NO_BRACKET) {
-          write_invalid(fields, stride, base + d);
-          write_invalid(fields, stride, base + d + half);
-          status[base + d] = st;
-          status[base + d + half] = st;
+          write_invalid(fields, stride, e0);
+          write_invalid(fields, stride, e1);
+          status[e0] = st;
+          status[e1] = st;
           continue;
         }
         if (!(e.A >= 0.0) || !isfinite(e.V) || !(e.V > 0.0)) st |= ORC_ST_NONPHYS;
-        write_entry(fields, stride, base + d, &e, m.tilt);
-        status[base + d] = st;
+        write_entry(fields, stride, e0, &e, m.tilt);
+        status[e0] = st;
         /* centrosymmetric copy: the reversed ray direction has the same
          * ray quantities; the slowness direction turns by pi */
         entry_t r = e;
-        r.r1 = -e.r1;
-        r.r3 = -e.r3;
         r.thR = e.thR + ORC_PI;
         if (r.thR >= 2.0 * ORC_PI) r.thR -= 2.0 * ORC_PI;
-        write_entry(fields, stride, base + d + half, &r, m.tilt);
+        write_entry(fields, stride, e1, &r, m.tilt);
         /* exact negation of the already-rotated direction */
-        fields[F_RX * stride + base + d + half] = -fields[F_RX * stride + base + d];
-        fields[F_RZ * stride + base + d + half] = -fields[F_RZ * stride + base + d];
-        status[base + d + half] = st;
+        fields[F_RX * stride + e1] = -fields[F_RX * stride + e0];
+        fields[F_RZ * stride + e1] = -fields[F_RZ * stride + e0];
+        status[e1] = st;
       }
     }
   }
   free(tab);
+  free(col);
   return 0;
+}
+
+int orc_build_cache_2d(const double *classes, long n_classes, int n_dirs,
+                       unsigned mode_mask, int reading, int n_sweep,
+                       double *fields, int32_t *status) {
+  return orc_build_cache_2d_cols(classes, n_classes, n_dirs, NULL, 0, mode_mask,
+                                 reading, n_sweep, fields, status);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -683,28 +703,33 @@ typedef struct {
   int n_off;
   const int32_t *ox, *oz, *bin;
   const double *L;
-  const int32_t *cls;   /* node -> class */
-  int n_dirs;
-  const double *V, *A;  /* [class][dir] for one mode */
-  const int32_t *st;    /* [class][dir] */
+  const int32_t *cls;   /* node -> class; NULL: the class is the node */
+  int n_cols;           /* cache columns */
+  const int32_t *col;   /* direction -> column */
+  const double *V, *A;  /* [class][column] for one mode */
+  const int32_t *st;    /* [class][column] */
 } graph_t;
 
-static int entry_usable(const graph_t *g, long k, int b) {
-  int32_t s = g->st[k * g->n_dirs + b];
+static long class_of(const graph_t *g, long node) {
+  return g->cls ? g->cls[node] : node;
+}
+
+static int entry_usable(const graph_t *g, long k, int c) {
+  int32_t s = g->st[k * g->n_cols + c];
   return !(s & (ORC_ST_NO_BRACKET | ORC_ST_FLUID | ORC_ST_NONPHYS));
 }
 
 /* eq 29 / eq 30 with endpoint averages (eq 28); field 0 = propagation,
  * field 1 = attenuation.  Not usable -> +inf. */
 static double edge_weight(const graph_t *g, int field, long i, long j, int o) {
-  long ki = g->cls[i], kj = g->cls[j];
-  int b = g->bin[o];
-  if (!entry_usable(g, ki, b) || !entry_usable(g, kj, b)) return INFINITY;
+  long ki = class_of(g, i), kj = class_of(g, j);
+  int c = g->col[g->bin[o]];
+  if (!entry_usable(g, ki, c) || !entry_usable(g, kj, c)) return INFINITY;
   if (field == 0) {
-    double vbar = 0.5 * (g->V[ki * g->n_dirs + b] + g->V[kj * g->n_dirs + b]);
+    double vbar = 0.5 * (g->V[ki * g->n_cols + c] + g->V[kj * g->n_cols + c]);
     return g->L[o] / vbar;
   }
-  double abar = 0.5 * (g->A[ki * g->n_dirs + b] + g->A[kj * g->n_dirs + b]);
+  double abar = 0.5 * (g->A[ki * g->n_cols + c] + g->A[kj * g->n_cols + c]);
   return g->L[o] * abar;
 }
 
@@ -803,14 +828,20 @@ static int predecessors(const graph_t *g, int field, long src,
 /* Trace one source for one mode on a 2D grid with a class cache.
  * V, A, st: [n_classes][n_dirs] slices of the chosen mode.
  * Any output pointer may be NULL.  tstar needs tauR's tree (pred_p). */
-int orc_trace_2d(long nx, long nz, double hx, double hz,
-                 const int32_t *class_id, int R, int n_dirs,
-                 const double *V, const double *A, const int32_t *st,
-                 long src, double *tauR, double *tauI, int32_t *predP,
-                 int32_t *predA, double *tstar, int32_t *hopP,
-                 int32_t *hopA) {
+int orc_trace_2d_cols(long nx, long nz, double hx, double hz,
+                      const int32_t *class_id, int R, int n_dirs,
+                      const int32_t *subset, int n_subset,
+                      const double *V, const double *A, const int32_t *st,
+                      long src, double *tauR, double *tauI, int32_t *predP,
+                      int32_t *predA, double *tstar, int32_t *hopP,
+                      int32_t *hopA) {
   long n = nx * nz;
   if (src < 0 || src >= n || R < 1) return 1;
+  int32_t *col = (int32_t *)malloc(sizeof(int32_t) * (size_t)n_dirs);
+  if (!col) return 2;
+  for (int d = 0; d < n_dirs; ++d) col[d] = subset ? -1 : d;
+  if (subset)
+    for (int q = 0; q < n_subset; ++q) col[subset[q]] = q;
   int n_off = orc_star_2d(R, hx, hz, n_dirs, NULL, NULL, NULL, NULL);
   int32_t *ox = (int32_t *)malloc(sizeof(int32_t) * n_off);
   int32_t *oz = (int32_t *)malloc(sizeof(int32_t) * n_off);
@@ -831,7 +862,10 @@ int orc_trace_2d(long nx, long nz, double hx, double hz,
     goto out;
   }
   orc_star_2d(R, hx, hz, n_dirs, ox, oz, L, bin);
-  graph_t g = {nx, nz, n_off, ox, oz, bin, L, class_id, n_dirs, V, A, st};
+  for (int o = 0; o < n_off; ++o)
+    if (col[bin[o]] < 0) { rc = 3; goto out; } /* cache lacks a star direction */
+  graph_t g = {nx, nz, n_off, ox, oz, bin, L, class_id,
+               subset ? n_subset : n_dirs, col, V, A, st};
   long nrP = 0, nrA = 0;
   if (dijkstra(&g, 0, src, tR) || dijkstra(&g, 1, src, tI)) { rc = 2; goto out; }
   predecessors(&g, 0, src, tR, pP, hP, ordP, &nrP);
@@ -860,8 +894,18 @@ int orc_trace_2d(long nx, long nz, double hx, double hz,
   if (hopA) memcpy(hopA, hA, sizeof(int32_t) * (size_t)n);
 out:
   free(ox); free(oz); free(bin); free(L); free(tR); free(tI);
-  free(pP); free(pA); free(hP); free(hA); free(ordP); free(ordA);
+  free(pP); free(pA); free(hP); free(hA); free(ordP); free(ordA); free(col);
   return rc;
+}
+
+int orc_trace_2d(long nx, long nz, double hx, double hz,
+                 const int32_t *class_id, int R, int n_dirs,
+                 const double *V, const double *A, const int32_t *st,
+                 long src, double *tauR, double *tauI, int32_t *predP,
+                 int32_t *predA, double *tstar, int32_t *hopP,
+                 int32_t *hopA) {
+  return orc_trace_2d_cols(nx, nz, hx, hz, class_id, R, n_dirs, NULL, 0, V, A,
+                           st, src, tauR, tauI, predP, predA, tstar, hopP, hopA);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -29,7 +29,7 @@ OUT_TAU_R, OUT_TAU_I, OUT_TSTAR, OUT_PRED_P, OUT_PRED_A = 1, 2, 4, 8, 16
 OUT_ALL = 31
 
 EXPORTS = (
-    "chert_class_from_thomsen", "chert_cache_layout_of",
+    "chert_class_from_thomsen", "chert_classes_from_thomsen", "chert_cache_layout_of",
     "chert_build_cache_workspace_bytes", "chert_build_cache",
     "chert_trace_workspace_bytes", "chert_trace_field",
     "chert_trace_batch_workspace_bytes", "chert_trace_batch",
@@ -56,7 +56,12 @@ class ChertClass(ctypes.Structure):
 class CacheDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n_dirs", ctypes.c_int32),
                 ("mode_mask", ctypes.c_uint32), ("kernel", ctypes.c_int32),
-                ("n_sweep", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("n_sweep", ctypes.c_int32), ("n_subset", ctypes.c_int32),
+                ("subset_host", ctypes.c_void_p)]
+
+    @property
+    def n_cols(self):
+        return self.n_subset if self.n_subset else self.n_dirs
 
 
 class CacheLayout(ctypes.Structure):
@@ -124,6 +129,7 @@ def lib():
                               ctypes.c_size_t, ctypes.c_double)
         L.chert_last_error.restype = ctypes.c_char_p
         L.chert_class_from_thomsen.argtypes = [d] * 10 + [P]
+        L.chert_classes_from_thomsen.argtypes = [P, i64, P, P]
         L.chert_cache_layout_of.argtypes = [P, i64, P]
         L.chert_build_cache_workspace_bytes.argtypes = [P, i64]
         L.chert_build_cache_workspace_bytes.restype = sz
@@ -175,11 +181,24 @@ def chert_class_from_thomsen(vp0, vs0, rho, eps, delta, gamma, tilt, azimuth, qp
     return out
 
 
-def cache_desc(n_dirs=360, modes=(QP, QSV, QSH), kernel=KERNEL_MEV, n_sweep=1440, dim=2):
+def cache_desc(n_dirs=360, modes=(QP, QSV, QSH), kernel=KERNEL_MEV, n_sweep=1440, dim=2,
+               subset=None):
+    """subset: ascending direction indices closed under reversal (kept
+    referenced by the descriptor), e.g. star_subset(radius, hx, hz)."""
     mask = 0
     for m in modes:
         mask |= 1 << m
-    return CacheDesc(dim, n_dirs, mask, kernel, n_sweep, 0)
+    if subset is None:
+        return CacheDesc(dim, n_dirs, mask, kernel, n_sweep, 0, None)
+    sub = np.ascontiguousarray(subset, dtype=np.int32)
+    d = CacheDesc(dim, n_dirs, mask, kernel, n_sweep, int(sub.size), sub.ctypes.data)
+    d._subset = sub
+    return d
+
+
+def star_subset(radius, hx, hz, n_dirs=360):
+    """Directions a forward star of this radius reads (sorted, unique)."""
+    return np.unique(chert_star_2d(radius, hx, hz, n_dirs)[3]).astype(np.int32)
 
 
 def chert_cache_layout_of(desc, n_classes):
@@ -229,6 +248,13 @@ def raypath_length(pred, src, rcv):
 
 # ----------------------------------------------------------- device calls --
 
+def chert_classes_from_thomsen(params_dev, classes_out_dev, stream=None):
+    """params_dev: float64 device tensor [n, 10]; classes_out_dev: float64
+    device tensor [n, 13] (the chert_class layout)."""
+    n = params_dev.shape[0]
+    _check(lib().chert_classes_from_thomsen(_ptr(params_dev), n, _ptr(classes_out_dev),
+                                            _stream(stream)))
+
 def chert_build_cache(desc, classes_dev, n_classes, cache_dev, workspace_dev, stream=None):
     """classes_dev: float64 device tensor [K, 13]; cache_dev: uint8 device
     tensor of the layout's total_bytes; workspace_dev: uint8 device tensor."""
@@ -238,7 +264,9 @@ def chert_build_cache(desc, classes_dev, n_classes, cache_dev, workspace_dev, st
 
 
 def make_grid(nx, nz, hx, hz, radius, class_id_dev):
-    g = Grid(2, radius, nx, nz, 1, hx, hz, 0.0, class_id_dev.data_ptr())
+    """class_id_dev None: the cache holds one class per node (index = node)."""
+    g = Grid(2, radius, nx, nz, 1, hx, hz, 0.0,
+             class_id_dev.data_ptr() if class_id_dev is not None else None)
     g._keep = class_id_dev  # the struct holds a raw pointer
     return g
 
@@ -322,11 +350,11 @@ def cache_views(cache_dev, desc, n_classes):
     """(fields [NF][3][K][n_dirs] float64, status [3][K][n_dirs] int32) views
     into a cache blob tensor, following the documented layout."""
     lay = chert_cache_layout_of(desc, n_classes)
-    n = 3 * n_classes * desc.n_dirs
+    n = 3 * n_classes * desc.n_cols
     f = cache_dev[lay.fields_offset: lay.fields_offset + NF * n * 8]
     s = cache_dev[lay.status_offset: lay.status_offset + n * 4]
-    return (f.view(dtype=_torch().float64).view(NF, 3, n_classes, desc.n_dirs),
-            s.view(dtype=_torch().int32).view(3, n_classes, desc.n_dirs))
+    return (f.view(dtype=_torch().float64).view(NF, 3, n_classes, desc.n_cols),
+            s.view(dtype=_torch().int32).view(3, n_classes, desc.n_cols))
 
 
 def _torch():

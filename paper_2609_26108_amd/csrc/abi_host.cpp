@@ -11,6 +11,8 @@
 #include "chert.h"
 #include "chert_internal.h"
 
+#pragma clang fp contract(off)
+
 namespace chert {
 
 static thread_local char g_err[512] = "";
@@ -168,6 +170,49 @@ extern "C" int chert_class_from_thomsen(double vp0, double vs0, double rho, doub
   return CHERT_OK;
 }
 
+// Device batch of the constitutive step for per-node media.  Same relations
+// and operation order as chert_class_from_thomsen (this file is built
+// without floating-point contraction, so both agree bitwise).
+__global__ void k_classes_from_thomsen(const double* p, int64_t n, chert_class* out) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const double* r = p + 10 * t;
+    const double vp0 = r[0], vs0 = r[1], rho = r[2], eps = r[3], delta = r[4], gamma = r[5];
+    const double tilt = r[6], azimuth = r[7], qp = r[8], qs = r[9];
+    bool ok = true;
+    for (int i = 0; i < 10; ++i) ok = ok && !isnan(r[i]);
+    ok = ok && vp0 > 0.0 && vs0 >= 0.0 && vs0 < vp0 && qp > 0.0 && qs > 0.0;
+    const double a33 = vp0 * vp0;
+    const double a44 = vs0 * vs0;
+    const double rad = 2.0 * delta * a33 * (a33 - a44) + (a33 - a44) * (a33 - a44);
+    ok = ok && rad >= 0.0;
+    chert_class c;
+    c.a11 = ok ? a33 * (1.0 + 2.0 * eps) : NAN;
+    c.a13 = ok ? sqrt(rad) - a44 : NAN;
+    c.a33 = ok ? a33 : NAN;
+    c.a44 = ok ? a44 : NAN;
+    c.a66 = ok ? a44 * (1.0 + 2.0 * gamma) : NAN;
+    c.q11 = c.q13 = c.q33 = qp;
+    c.q44 = c.q66 = qs;
+    c.rho = rho;
+    c.tilt = tilt;
+    c.azimuth = azimuth;
+    out[t] = c;
+  }
+}
+
+extern "C" int chert_classes_from_thomsen(const double* params_dev, int64_t n,
+                                          chert_class* out_dev, void* stream) {
+  if (!params_dev || !out_dev || n <= 0) return fail(CHERT_ERR_INVALID_ARG, "bad arguments");
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  CHERT_LAUNCH("k_classes_from_thomsen", k_classes_from_thomsen, dim3((unsigned)blocks),
+               dim3(256), 0, (hipStream_t)stream, params_dev, n, out_dev);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+  return CHERT_OK;
+}
+
 extern "C" int chert_cache_layout_of(const chert_cache_desc* d, int64_t n_classes,
                                      chert_cache_layout* out) {
   if (!d || !out) return fail(CHERT_ERR_INVALID_ARG, "null desc or output");
@@ -178,9 +223,28 @@ extern "C" int chert_cache_layout_of(const chert_cache_desc* d, int64_t n_classe
   if (d->kernel != CHERT_KERNEL_MEV && d->kernel != CHERT_KERNEL_OEV)
     return fail(CHERT_ERR_INVALID_ARG, "bad kernel");
   if (d->n_sweep < 16) return fail(CHERT_ERR_INVALID_ARG, "n_sweep must be >= 16");
-  if (d->reserved != 0) return fail(CHERT_ERR_INVALID_ARG, "reserved must be 0");
   if (n_classes <= 0) return fail(CHERT_ERR_INVALID_ARG, "n_classes must be positive");
-  size_t entries = (size_t)3 * (size_t)n_classes * (size_t)d->n_dirs;
+  if (d->n_subset != 0) {
+    if (d->n_subset < 0 || d->n_subset > kMaxSubset || !d->subset_host || (d->n_subset & 1))
+      return fail(CHERT_ERR_INVALID_ARG, "subset needs 2..512 (even) directions");
+    const int half = d->n_dirs / 2;
+    for (int i = 0; i < d->n_subset; ++i) {
+      int b = d->subset_host[i];
+      if (b < 0 || b >= d->n_dirs || (i > 0 && b <= d->subset_host[i - 1]))
+        return fail(CHERT_ERR_INVALID_ARG, "subset must be ascending directions in range");
+      // partner b + half (mod n_dirs) must be present
+      int pb = (b + half) % d->n_dirs, lo = 0, hi = d->n_subset - 1;
+      while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (d->subset_host[mid] < pb) lo = mid + 1;
+        else hi = mid;
+      }
+      if (d->subset_host[lo] != pb)
+        return fail(CHERT_ERR_INVALID_ARG, "subset not closed under reversal");
+    }
+  }
+  const int n_cols = d->n_subset ? d->n_subset : d->n_dirs;
+  size_t entries = (size_t)3 * (size_t)n_classes * (size_t)n_cols;
   out->fields_offset = kHeaderBytes;
   out->status_offset = kHeaderBytes + entries * CHERT_NF * sizeof(double);
   size_t end = out->status_offset + entries * sizeof(int32_t);

@@ -77,9 +77,27 @@ struct SolveArgs {
   int n_sweep;
   int n_dirs;
   const double2* table;
-  double* fields;   // [CHERT_NF][3][n_classes][n_dirs]
-  int32_t* status;  // [3][n_classes][n_dirs]
+  double* fields;   // [CHERT_NF][3][n_classes][n_cols]
+  int32_t* status;  // [3][n_classes][n_cols]
+  int n_cols;       // stored direction columns per (mode, class)
+  int n_solve;      // directions solved per (mode, class); the rest are copies
+  int subset;       // 0: every direction d < n_dirs/2, column d, copy at d + n_dirs/2
+  int16_t dir[kMaxSubset / 2];   // solved direction (subset caches)
+  int16_t col[kMaxSubset / 2];   // its column
+  int16_t pcol[kMaxSubset / 2];  // column of the reversed direction
 };
+
+__device__ __forceinline__ void dir_cols(const SolveArgs& a, int s, int* d, int* c, int* pc) {
+  if (!a.subset) {
+    *d = s;
+    *c = s;
+    *pc = s + a.n_dirs / 2;
+  } else {
+    *d = a.dir[s];
+    *c = a.col[s];
+    *pc = a.pcol[s];
+  }
+}
 
 // Newton on F = (h, psi - psi*) from the bracket interpolant.  Elastic modes
 // keep theta_I = 0 exactly and solve the 1D direction equation.
@@ -227,11 +245,74 @@ __device__ __forceinline__ bool is_bracket(const double2* tab, int j, int n, dou
   return brackets(fa, fb);
 }
 
+// Solve target direction d for one (class, mode) from its sweep table in
+// LDS.  Lanes of a wavefront run it in step (brackets first, then the
+// refinements together); `br` is this lane's kMaxBr bracket slots in LDS.
+__device__ __forceinline__ int32_t solve_dir(const SolveArgs& a, const Medium& m, int mode,
+                                             const double2* tab, int d, int* br, Entry* best) {
+  const bool el = theta_i_zero(m, mode);
+  const double psi_star = wrap_pi(d * (kTwoPi / a.n_dirs) - m.tilt);
+  // phase 1: every sign change of the ray-direction miss over the sweep
+  int nbr = 0;
+  for (int j = 0; j < a.n_sweep; ++j) {
+    if (!is_bracket(tab, j, a.n_sweep, psi_star)) continue;
+    if (nbr < kMaxBr) br[nbr] = j;
+    ++nbr;
+  }
+  // phase 2: refine the kept brackets with all lanes in step
+  bool found = false, ill = false;
+  for (int sidx = 0; sidx < kMaxBr; ++sidx) {
+    if (__all(sidx >= nbr)) break;
+    if (sidx < nbr) refine_bracket(a, m, mode, tab, br[sidx], psi_star, el, &found, &ill, best);
+  }
+  // rare: more brackets than slots; refine the rest in scan order
+  if (nbr > kMaxBr) {
+    int seen = 0;
+    for (int j = 0; j < a.n_sweep; ++j) {
+      if (!is_bracket(tab, j, a.n_sweep, psi_star)) continue;
+      if (seen++ < kMaxBr) continue;
+      refine_bracket(a, m, mode, tab, j, psi_star, el, &found, &ill, best);
+    }
+  }
+  if (!found) return CHERT_ST_NO_BRACKET;
+  int32_t st = ill ? CHERT_ST_ILL : CHERT_ST_OK;
+  if (!(best->A >= 0.0) || !isfinite(best->V) || !(best->V > 0.0)) st |= CHERT_ST_NONPHYS;
+  return st;
+}
+
+// Write the solved entry and its centrosymmetric copy (same ray quantities,
+// reversed direction, slowness direction turned by pi).
+__device__ __forceinline__ void store_pair(const SolveArgs& a, int64_t row, int col, int pcol,
+                                           const Entry& best, double tilt, int32_t st) {
+  const int64_t stride = 3 * a.n_classes * (int64_t)a.n_cols;
+  if (st & (CHERT_ST_NO_BRACKET | CHERT_ST_FLUID) || (st == CHERT_ST_NONPHYS && isnan(best.V))) {
+    store_invalid(a, row + col, stride, st);
+    store_invalid(a, row + pcol, stride, st);
+    return;
+  }
+  store_entry(a, row + col, stride, best, tilt, st);
+  Entry r = best;
+  r.thR = best.thR + kPi;
+  if (r.thR >= kTwoPi) r.thR -= kTwoPi;
+  store_entry(a, row + pcol, stride, r, tilt, st);
+  a.fields[CHERT_F_RX * stride + row + pcol] = -a.fields[CHERT_F_RX * stride + row + col];
+  a.fields[CHERT_F_RZ * stride + row + pcol] = -a.fields[CHERT_F_RZ * stride + row + col];
+}
+
+// Entries of a class that cannot be solved (invalid parameters, or a shear
+// mode without shear stiffness).
+__device__ __forceinline__ int32_t class_block(const chert_class& c, int mode) {
+  if (class_invalid(c)) return CHERT_ST_NONPHYS;
+  if (is_fluid_shear(c, mode)) return CHERT_ST_FLUID;
+  return 0;
+}
+
+// Two-launch path (few classes): one workgroup per (mode, class, 64
+// directions), sweep table from k_sweep staged in LDS.
 __global__ void __launch_bounds__(64) k_solve(SolveArgs a) {
   extern __shared__ double2 tab[];
   __shared__ int s_br[64 * kMaxBr];
-  const int half = a.n_dirs / 2;
-  const int chunks = (half + 63) / 64;
+  const int chunks = (a.n_solve + 63) / 64;
   const int64_t job = blockIdx.x / chunks;
   const int chunk = blockIdx.x % chunks;
   const int64_t k = job % a.n_classes;
@@ -240,69 +321,71 @@ __global__ void __launch_bounds__(64) k_solve(SolveArgs a) {
   for (int j = threadIdx.x; j < a.n_sweep; j += blockDim.x) tab[j] = src[j];
   __syncthreads();
 
-  const int d = chunk * 64 + threadIdx.x;
-  if (d >= half) return;
-  const int64_t stride = 3 * a.n_classes * (int64_t)a.n_dirs;
-  const int64_t base = ((int64_t)mode * a.n_classes + k) * a.n_dirs + d;
+  const int sidx = chunk * 64 + threadIdx.x;
+  if (sidx >= a.n_solve) return;
+  int d, col, pcol;
+  dir_cols(a, sidx, &d, &col, &pcol);
+  const int64_t row = ((int64_t)mode * a.n_classes + k) * a.n_cols;
   const chert_class c = a.classes[k];
-  if (class_invalid(c)) {
-    store_invalid(a, base, stride, CHERT_ST_NONPHYS);
-    store_invalid(a, base + half, stride, CHERT_ST_NONPHYS);
-    return;
-  }
-  if (is_fluid_shear(c, mode)) {
-    store_invalid(a, base, stride, CHERT_ST_FLUID);
-    store_invalid(a, base + half, stride, CHERT_ST_FLUID);
+  Entry best{};
+  best.V = NAN;
+  int32_t st = class_block(c, mode);
+  if (st) {
+    store_pair(a, row, col, pcol, best, 0.0, st);
     return;
   }
   const Medium m = load_medium(c);
-  const bool el = theta_i_zero(m, mode);
-  const double psi_star = wrap_pi(d * (kTwoPi / a.n_dirs) - m.tilt);
+  st = solve_dir(a, m, mode, tab, d, s_br + threadIdx.x * kMaxBr, &best);
+  store_pair(a, row, col, pcol, best, m.tilt, st);
+}
 
-  // phase 1: every sign change of the ray-direction miss over the sweep
-  int nbr = 0;
-  int* my = s_br + threadIdx.x * kMaxBr;
-  for (int j = 0; j < a.n_sweep; ++j) {
-    if (!is_bracket(tab, j, a.n_sweep, psi_star)) continue;
-    if (nbr < kMaxBr) my[nbr] = j;
-    ++nbr;
-  }
-  // phase 2: refine the kept brackets with all lanes in step
-  bool found = false, ill = false;
-  Entry best{};
-  for (int sidx = 0; sidx < kMaxBr; ++sidx) {
-    if (__all(sidx >= nbr)) break;
-    if (sidx < nbr) refine_bracket(a, m, mode, tab, my[sidx], psi_star, el, &found, &ill, &best);
-  }
-  // rare: more brackets than slots; refine the rest in scan order
-  if (nbr > kMaxBr) {
-    int seen = 0;
-    for (int j = 0; j < a.n_sweep; ++j) {
-      if (!is_bracket(tab, j, a.n_sweep, psi_star)) continue;
-      if (seen++ < kMaxBr) continue;
-      refine_bracket(a, m, mode, tab, j, psi_star, el, &found, &ill, &best);
+// Fused path (many classes, e.g. one per node): one workgroup per
+// (mode, class) sweeps theta_R into LDS, then solves that class's
+// directions; no sweep table in HBM.
+constexpr int kNodeThreads = 256;
+__global__ void __launch_bounds__(kNodeThreads) k_build_fused(SolveArgs a) {
+  extern __shared__ double2 tab[];
+  __shared__ int s_br[kNodeThreads * kMaxBr];
+  const int64_t job = blockIdx.x;
+  const int64_t k = job % a.n_classes;
+  const int mode = a.modes[job / a.n_classes];
+  const chert_class c = a.classes[k];
+  const int64_t row = ((int64_t)mode * a.n_classes + k) * a.n_cols;
+  int32_t blocked = class_block(c, mode);
+  if (blocked) {
+    Entry none{};
+    none.V = NAN;
+    for (int sidx = threadIdx.x; sidx < a.n_solve; sidx += blockDim.x) {
+      int d, col, pcol;
+      dir_cols(a, sidx, &d, &col, &pcol);
+      store_pair(a, row, col, pcol, none, 0.0, blocked);
     }
+    return;  // block-uniform
   }
-  if (!found) {
-    store_invalid(a, base, stride, CHERT_ST_NO_BRACKET);
-    store_invalid(a, base + half, stride, CHERT_ST_NO_BRACKET);
-    return;
+  const Medium m = load_medium(c);
+  for (int j = threadIdx.x; j < a.n_sweep; j += blockDim.x) {
+    const double thR = (j + 0.5) * (kTwoPi / a.n_sweep);
+    double thI;
+    double2 out = make_double2(0.0, NAN);
+    if (theta_imag(m, mode, a.kernel, thR, &thI)) {
+      const double psi = ray_angle(energy_velocity(m, mode, a.kernel, thR, thI));
+      if (isfinite(psi)) out = make_double2(thI, psi);
+    }
+    tab[j] = out;
   }
-  int32_t st = ill ? CHERT_ST_ILL : CHERT_ST_OK;
-  if (!(best.A >= 0.0) || !isfinite(best.V) || !(best.V > 0.0)) st |= CHERT_ST_NONPHYS;
-  store_entry(a, base, stride, best, m.tilt, st);
-  // centrosymmetric copy: same ray quantities, reversed direction, slowness
-  // direction turned by pi
-  Entry r = best;
-  r.thR = best.thR + kPi;
-  if (r.thR >= kTwoPi) r.thR -= kTwoPi;
-  store_entry(a, base + half, stride, r, m.tilt, st);
-  a.fields[CHERT_F_RX * stride + base + half] = -a.fields[CHERT_F_RX * stride + base];
-  a.fields[CHERT_F_RZ * stride + base + half] = -a.fields[CHERT_F_RZ * stride + base];
+  __syncthreads();
+  for (int sidx = threadIdx.x; sidx < a.n_solve; sidx += blockDim.x) {
+    int d, col, pcol;
+    dir_cols(a, sidx, &d, &col, &pcol);
+    Entry best{};
+    const int32_t st = solve_dir(a, m, mode, tab, d, s_br + threadIdx.x * kMaxBr, &best);
+    store_pair(a, row, col, pcol, best, m.tilt, st);
+  }
 }
 
 __global__ void k_write_header(uint8_t* cache, int32_t dim, int32_t n_dirs, uint32_t mask,
-                               int32_t kernel, int32_t n_sweep, int64_t n_classes) {
+                               int32_t kernel, int32_t n_sweep, int32_t n_subset,
+                               int64_t n_classes) {
   int t = threadIdx.x;
   uint32_t* w = reinterpret_cast<uint32_t*>(cache);
   if (t < 64) w[t] = 0u;
@@ -315,7 +398,7 @@ __global__ void k_write_header(uint8_t* cache, int32_t dim, int32_t n_dirs, uint
     w[4] = mask;
     w[5] = (uint32_t)kernel;
     w[6] = (uint32_t)n_sweep;
-    w[7] = 0u;
+    w[7] = (uint32_t)n_subset;
     *reinterpret_cast<int64_t*>(cache + 32) = n_classes;
   }
 }
@@ -324,11 +407,18 @@ __global__ void k_write_header(uint8_t* cache, int32_t dim, int32_t n_dirs, uint
 
 using namespace chert;
 
+// Jobs (mode x class) at or above this count use the fused one-launch path.
+constexpr int64_t kFusedJobs = 512;
+
+static int64_t n_jobs_of(const chert_cache_desc* d, int64_t n_classes) {
+  return (int64_t)__builtin_popcount(d->mode_mask & 7u) * n_classes;
+}
+
 extern "C" size_t chert_build_cache_workspace_bytes(const chert_cache_desc* d,
                                                     int64_t n_classes) {
   if (!d || n_classes <= 0 || d->n_sweep <= 0) return 0;
-  int nm = __builtin_popcount(d->mode_mask & 7u);
-  return (size_t)nm * (size_t)n_classes * (size_t)d->n_sweep * sizeof(double2);
+  if (n_jobs_of(d, n_classes) >= kFusedJobs) return 0;  // sweep table stays in LDS
+  return (size_t)n_jobs_of(d, n_classes) * (size_t)d->n_sweep * sizeof(double2);
 }
 
 extern "C" int chert_build_cache(const chert_cache_desc* d, const chert_class* classes_dev,
@@ -340,46 +430,71 @@ extern "C" int chert_build_cache(const chert_cache_desc* d, const chert_class* c
   if (!classes_dev || !cache_dev) return fail(CHERT_ERR_INVALID_ARG, "null classes or cache");
   if (d->n_sweep > kMaxSweep)
     return fail(CHERT_ERR_INVALID_ARG, "n_sweep above the LDS table limit");
-  size_t need = chert_build_cache_workspace_bytes(d, n_classes);
-  if (!workspace_dev || workspace_bytes < need)
+  const size_t need = chert_build_cache_workspace_bytes(d, n_classes);
+  if (need > 0 && (!workspace_dev || workspace_bytes < need))
     return fail(CHERT_ERR_INVALID_ARG, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
   uint8_t* cache = (uint8_t*)cache_dev;
 
-  SweepArgs sa{};
-  sa.classes = classes_dev;
-  sa.n_classes = n_classes;
-  sa.n_modes = 0;
+  int modes[3], n_modes = 0;
   for (int m = 0; m < 3; ++m)
-    if (d->mode_mask & (1u << m)) sa.modes[sa.n_modes++] = m;
-  sa.kernel = d->kernel;
-  sa.n_sweep = d->n_sweep;
-  sa.table = (double2*)workspace_dev;
+    if (d->mode_mask & (1u << m)) modes[n_modes++] = m;
 
-  CHERT_LAUNCH("k_write_header", k_write_header, dim3(1), dim3(64), 0, s, cache, d->dim, d->n_dirs,
-                     d->mode_mask, d->kernel, d->n_sweep, n_classes);
-  if (sa.n_modes > 0) {
-    int64_t total = (int64_t)sa.n_modes * n_classes * d->n_sweep;
+  SolveArgs so{};
+  so.classes = classes_dev;
+  so.n_classes = n_classes;
+  so.n_modes = n_modes;
+  for (int i = 0; i < 3; ++i) so.modes[i] = i < n_modes ? modes[i] : 0;
+  so.kernel = d->kernel;
+  so.n_sweep = d->n_sweep;
+  so.n_dirs = d->n_dirs;
+  so.table = (const double2*)workspace_dev;
+  so.fields = (double*)(cache + lay.fields_offset);
+  so.status = (int32_t*)(cache + lay.status_offset);
+  const int half = d->n_dirs / 2;
+  if (d->n_subset == 0) {
+    so.subset = 0;
+    so.n_cols = d->n_dirs;
+    so.n_solve = half;
+  } else {
+    so.subset = 1;
+    so.n_cols = d->n_subset;
+    so.n_solve = 0;
+    for (int i = 0; i < d->n_subset; ++i) {
+      const int b = d->subset_host[i];
+      if (b >= half) continue;
+      int p = 0;
+      while (d->subset_host[p] != b + half) ++p;  // present: validated
+      so.dir[so.n_solve] = (int16_t)b;
+      so.col[so.n_solve] = (int16_t)i;
+      so.pcol[so.n_solve] = (int16_t)p;
+      ++so.n_solve;
+    }
+  }
+
+  CHERT_LAUNCH("k_write_header", k_write_header, dim3(1), dim3(64), 0, s, cache, d->dim,
+               d->n_dirs, d->mode_mask, d->kernel, d->n_sweep, d->n_subset, n_classes);
+  const int64_t jobs = (int64_t)n_modes * n_classes;
+  if (jobs > 0x7fffffffLL) return fail(CHERT_ERR_INVALID_ARG, "too many classes");
+  if (jobs >= kFusedJobs) {
+    CHERT_LAUNCH("k_build_fused", k_build_fused, dim3((unsigned)jobs), dim3(kNodeThreads),
+                 (size_t)d->n_sweep * sizeof(double2), s, so);
+  } else if (jobs > 0) {
+    SweepArgs sa{};
+    sa.classes = classes_dev;
+    sa.n_classes = n_classes;
+    sa.n_modes = n_modes;
+    for (int i = 0; i < 3; ++i) sa.modes[i] = so.modes[i];
+    sa.kernel = d->kernel;
+    sa.n_sweep = d->n_sweep;
+    sa.table = (double2*)workspace_dev;
+    int64_t total = jobs * d->n_sweep;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     CHERT_LAUNCH("k_sweep", k_sweep, dim3((unsigned)blocks), dim3(256), 0, s, sa);
-
-    SolveArgs so{};
-    so.classes = classes_dev;
-    so.n_classes = n_classes;
-    so.n_modes = sa.n_modes;
-    for (int i = 0; i < 3; ++i) so.modes[i] = sa.modes[i];
-    so.kernel = d->kernel;
-    so.n_sweep = d->n_sweep;
-    so.n_dirs = d->n_dirs;
-    so.table = sa.table;
-    so.fields = (double*)(cache + lay.fields_offset);
-    so.status = (int32_t*)(cache + lay.status_offset);
-    int chunks = (d->n_dirs / 2 + 63) / 64;
-    int64_t grid = (int64_t)sa.n_modes * n_classes * chunks;
-    if (grid > 0x7fffffff) return fail(CHERT_ERR_INVALID_ARG, "too many classes");
-    CHERT_LAUNCH("k_solve", k_solve, dim3((unsigned)grid), dim3(64),
-                       (size_t)d->n_sweep * sizeof(double2), s, so);
+    const int chunks = (so.n_solve + 63) / 64;
+    CHERT_LAUNCH("k_solve", k_solve, dim3((unsigned)(jobs * chunks)), dim3(64),
+                 (size_t)d->n_sweep * sizeof(double2), s, so);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));

@@ -14,6 +14,7 @@ constexpr uint32_t kCacheVersion = 1u;
 constexpr size_t kHeaderBytes = 256;
 constexpr int kMaxSweep = 4096;  // sweep table staged in LDS: 64 KiB
 constexpr int kMaxRadius = 8;
+constexpr int kMaxSubset = 512;  // direction columns of a subset cache
 constexpr int kMaxOffsets = 288;  // (2R+1)^2 - 1 bound on |O_R| in 2D for R <= 8
 
 // Record a failure message for chert_last_error() and return the code.

@@ -53,11 +53,29 @@ constexpr int32_t kClassMask = 0x3fffffff;
 struct JobDev {
   int nx, nz;     // nodes (nx * nz < 2^31)
   int ntx, ntz;   // tiles per axis
-  int K;          // classes of the job's cache
+  int K;          // classes of the job's cache (class mode)
   int w_in_lds;   // stage W in LDS
+  int per_node;   // cache indexed by node: weights per (node, offset)
+  int pad;
   const int32_t* class_id;
-  const double* W;  // [2][K][K][n_off]: propagation then attenuation weights
+  const double* W;  // class mode: [2][K][K][n_off]; per-node: [2][n_nodes][n_off],
+                    // entry (j, o) = weight of the edge between j and j - o
 };
+
+// Weight of the edge i -> j = i + o (pull side: j is known; push side: i is
+// known and, by symmetry, row i at the reversed offset holds the same edge).
+__device__ __forceinline__ double w_pull(const JobDev& jb, const double* Wp, int field, int ki,
+                                         int kj, int o, int n_off, int64_t gj) {
+  if (jb.per_node)
+    return jb.W[((int64_t)field * jb.nx * jb.nz + gj) * n_off + o];
+  return Wp[(ki * jb.K + kj) * n_off + o];
+}
+__device__ __forceinline__ double w_push(const JobDev& jb, const double* Wp, int field, int ki,
+                                         int kj, int o, int n_off, int64_t gi) {
+  if (jb.per_node)
+    return jb.W[((int64_t)field * jb.nx * jb.nz + gi) * n_off + (n_off - 1 - o)];
+  return Wp[(ki * jb.K + kj) * n_off + o];
+}
 
 struct ProbDev {
   double* tau;     // [n_nodes] this problem's field
@@ -101,8 +119,8 @@ __device__ __forceinline__ void count_visit(const RelaxArgs& a, int phase, long 
 
 // W[f][ki][kj][o]: eqs 28-30 in this operation order, no contraction.
 __global__ void k_weights(double* W, int K, int n_off, const double* V, const double* A,
-                          const int32_t* st, int n_dirs, const double* L,
-                          const int32_t* bin) {
+                          const int32_t* st, int n_cols, const double* L,
+                          const int32_t* col) {
   int64_t total = 2LL * K * K * n_off;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
@@ -112,9 +130,9 @@ __global__ void k_weights(double* W, int K, int n_off, const double* V, const do
     r /= K;
     int ki = (int)(r % K);
     int f = (int)(r / K);
-    int b = bin[o];
+    const int b = col[o];
     const int bad = CHERT_ST_NO_BRACKET | CHERT_ST_FLUID | CHERT_ST_NONPHYS;
-    int64_t ei = (int64_t)ki * n_dirs + b, ej = (int64_t)kj * n_dirs + b;
+    int64_t ei = (int64_t)ki * n_cols + b, ej = (int64_t)kj * n_cols + b;
     double w;
     if ((st[ei] & bad) || (st[ej] & bad)) {
       w = INFINITY;
@@ -124,6 +142,36 @@ __global__ void k_weights(double* W, int K, int n_off, const double* V, const do
       w = __dmul_rn(L[o], __dmul_rn(0.5, __dadd_rn(A[ei], A[ej])));
     }
     W[t] = w;
+  }
+}
+
+// Per-node weights: W[f][j][o] for the edge between j - o and j (eqs 28-30),
+// with V, A, status indexed [node][column] and col[o] the cache column of
+// the offset's bin; out-of-grid neighbours give +inf.
+__global__ void k_weights_node(double* W, int nx, int nz, int n_off, const int32_t* ox,
+                               const int32_t* oz, const double* L, const int32_t* col,
+                               int n_cols, const double* V, const double* A,
+                               const int32_t* st) {
+  const int64_t n = (int64_t)nx * nz;
+  const int64_t total = n * n_off;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int o = (int)(t % n_off);
+    const int64_t j = t / n_off;
+    const int jx = (int)(j % nx), jz = (int)(j / nx);
+    const int ix = jx - ox[o], iz = jz - oz[o];
+    double wr = INFINITY, wi = INFINITY;
+    if (ix >= 0 && ix < nx && iz >= 0 && iz < nz) {
+      const int64_t i = (int64_t)ix + (int64_t)nx * iz;
+      const int64_t ei = i * n_cols + col[o], ej = j * n_cols + col[o];
+      const int bad = CHERT_ST_NO_BRACKET | CHERT_ST_FLUID | CHERT_ST_NONPHYS;
+      if (!(st[ei] & bad) && !(st[ej] & bad)) {
+        wr = __ddiv_rn(L[o], __dmul_rn(0.5, __dadd_rn(V[ei], V[ej])));
+        wi = __dmul_rn(L[o], __dmul_rn(0.5, __dadd_rn(A[ei], A[ej])));
+      }
+    }
+    W[t] = wr;
+    W[total + t] = wi;
   }
 }
 
@@ -290,7 +338,7 @@ __device__ __forceinline__ void load_common(const RelaxArgs& a, const TileCtx& c
     int gx = c.x0 + (q % lw) - R, gz = c.z0 + (q / lw) - R;
     int32_t k = -1;
     if (gx >= 0 && gx < jb.nx && gz >= 0 && gz < jb.nz) {
-      k = jb.class_id[(int64_t)gx + (int64_t)jb.nx * gz];
+      k = jb.per_node ? 0 : jb.class_id[(int64_t)gx + (int64_t)jb.nx * gz];
       if (k < 0 || k >= jb.K) {
         atomicAdd(a.err, 1);
         k = -2;
@@ -307,6 +355,7 @@ __device__ __forceinline__ void load_common(const RelaxArgs& a, const TileCtx& c
 
 __device__ __forceinline__ const double* stage_w(const RelaxArgs& a, const JobDev& jb, int field,
                                                  const Smem& s) {
+  if (jb.per_node) return jb.W;  // read per (node, offset) from HBM
   const int kk = jb.K * jb.K * a.n_off;
   const double* Wf = jb.W + (int64_t)field * kk;
   if (!jb.w_in_lds) return Wf;
@@ -357,6 +406,12 @@ __device__ __forceinline__ int seed_node(const RelaxArgs& a, const TileCtx& c, i
   return (sz + a.R) * a.lw + (sx + a.R);
 }
 
+// Global node index of LDS cell l.
+__device__ __forceinline__ int64_t gnode(const RelaxArgs& a, const TileCtx& c, const JobDev& jb,
+                                         int l) {
+  return (int64_t)(c.x0 + l % a.lw - a.R) + (int64_t)jb.nx * (c.z0 + l / a.lw - a.R);
+}
+
 // LDS index of this thread's interior node, or -1.
 __device__ __forceinline__ int my_node(const RelaxArgs& a, const TileCtx& c) {
   const int q = threadIdx.x;
@@ -405,14 +460,15 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_tau(RelaxArgs a, int ro
     if (ml >= 0 && pulls(a, c, ml)) {
       const int kj = s.cls[ml];
       if (kj >= 0) {
+        const int64_t gml = gnode(a, c, jb, ml);
         const double cur = s.val[ml];
         double best = cur;
         for (int o = 0; o < n_off; ++o) {
           const int ii = ml - s.off[o];
           const int ki = s.cls[ii];
           if (ki < 0) continue;
-          const double cand =
-              __dadd_rn(s.val[ii], Wp[((ki & kClassMask) * K + kj) * n_off + o]);
+          const double cand = __dadd_rn(
+              s.val[ii], w_pull(jb, Wp, pr.field, ki & kClassMask, kj, o, n_off, gml));
           if (cand < best) best = cand;
         }
         if (best < cur) {
@@ -458,11 +514,12 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_tau(RelaxArgs a, int ro
         const int o = g * G + u;
         if (live && o < n_off) {
           const double vi = s.val[i];
-          const double* Wi = Wp + (s.cls[i] & kClassMask) * K * n_off;
+          const int ki = s.cls[i] & kClassMask;
+          const int64_t gi = gnode(a, c, jb, i);
             const int j = i + s.off[o];
             const int kj = s.cls[j];
             if (kj >= 0 && !(kj & kHaloBit)) {
-              const double cand = __dadd_rn(vi, Wi[kj * n_off + o]);
+              const double cand = __dadd_rn(vi, w_push(jb, Wp, pr.field, ki, kj, o, n_off, gi));
               // plain read first: most pushes do not improve, skip their atomic
               if (cand < s.val[j]) {
                 const unsigned long long old =
@@ -539,6 +596,7 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_hop(RelaxArgs a, int ro
       const int kj = s.cls[ml];
       const double tj = s.val[ml];
       if (kj >= 0 && tj < INFINITY) {
+        const int64_t gml = gnode(a, c, jb, ml);
         const int32_t cur = s.ival[ml];
         int32_t best = cur;
         for (int o = 0; o < n_off; ++o) {
@@ -546,7 +604,8 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_hop(RelaxArgs a, int ro
           const int ki = s.cls[ii];
           const int32_t hi = s.ival[ii];
           if (ki < 0 || hi == kHopUnset || hi + 1 >= best) continue;
-          if (__dadd_rn(s.val[ii], Wp[((ki & kClassMask) * K + kj) * n_off + o]) == tj)
+          if (__dadd_rn(s.val[ii],
+                        w_pull(jb, Wp, pr.field, ki & kClassMask, kj, o, n_off, gml)) == tj)
             best = hi + 1;
         }
         if (best < cur) {
@@ -591,14 +650,15 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_hop(RelaxArgs a, int ro
         if (live && o < n_off) {
           const double vi = s.val[i];
           const int32_t cand = s.ival[i] + 1;
-          const double* Wi = Wp + (s.cls[i] & kClassMask) * K * n_off;
+          const int ki = s.cls[i] & kClassMask;
+          const int64_t gi = gnode(a, c, jb, i);
             const int j = i + s.off[o];
             const int kj = s.cls[j];
             if (kj >= 0 && !(kj & kHaloBit)) {
               const double tj = s.val[j];
               // tight edge into a reachable node (inf + w == inf is no edge)
               if (cand < s.ival[j] && tj < INFINITY &&
-                  __dadd_rn(vi, Wi[kj * n_off + o]) == tj) {
+                  __dadd_rn(vi, w_push(jb, Wp, pr.field, ki, kj, o, n_off, gi)) == tj) {
                 const int32_t old = atomicMin(&s.ival[j], cand);
                 if (cand < old) {
                   improved = atomicExch(&s.inq[j], it + 1) != it + 1;
@@ -641,13 +701,13 @@ __global__ void k_pred(RelaxArgs a) {
   const JobDev jb = a.jobs[pr.job];
   const int K = jb.K, n_off = a.n_off;
   const int64_t n_nodes = (int64_t)jb.nx * jb.nz;
-  const double* Wf = jb.W + (int64_t)pr.field * K * K * n_off;
+  const double* Wf = jb.per_node ? jb.W : jb.W + (int64_t)pr.field * K * K * n_off;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_nodes;
        j += (int64_t)gridDim.x * blockDim.x) {
     const int32_t hj = pr.hop[j];
     int32_t best = -1;
     const int jx = (int)(j % jb.nx), jz = (int)(j / jb.nx);
-    const int32_t kj = jb.class_id[j];
+    const int32_t kj = jb.per_node ? 0 : jb.class_id[j];
     if (j != pr.src && hj != kHopUnset && kj >= 0 && kj < K) {
       const double tj = pr.tau[j];
       for (int o = 0; o < n_off; ++o) {
@@ -655,9 +715,9 @@ __global__ void k_pred(RelaxArgs a) {
         if (ix < 0 || ix >= jb.nx || iz < 0 || iz >= jb.nz) continue;
         int64_t i = (int64_t)ix + (int64_t)jb.nx * iz;
         if (pr.hop[i] != hj - 1) continue;
-        int32_t ki = jb.class_id[i];
+        int32_t ki = jb.per_node ? 0 : jb.class_id[i];
         if (ki < 0 || ki >= K) continue;
-        if (__dadd_rn(pr.tau[i], Wf[(ki * K + kj) * n_off + o]) == tj) {
+        if (__dadd_rn(pr.tau[i], w_pull(jb, Wf, pr.field, ki, kj, o, n_off, j)) == tj) {
           best = (int32_t)i;
           break;
         }
@@ -733,7 +793,8 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_tstar(RelaxArgs a, int 
         const int ii = ml - s.off[o];
         const double tp = s.val[ii];
         if (!isnan(tp)) {
-          s.val[ml] = __dadd_rn(tp, WI[((s.cls[ii] & kClassMask) * K + s.cls[ml]) * n_off + o]);
+          s.val[ml] = __dadd_rn(tp, w_pull(jb, WI, kFieldI, s.cls[ii] & kClassMask, s.cls[ml],
+                                           o, n_off, gnode(a, c, jb, ml)));
           known = true;
         }
       }
@@ -772,13 +833,15 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_tstar(RelaxArgs a, int 
         const int o = g * G + u;
         if (live && o < n_off) {
           const double vi = s.val[i];
-          const double* Wi = WI + (s.cls[i] & kClassMask) * K * n_off;
+          const int ki = s.cls[i] & kClassMask;
+          const int64_t gi = gnode(a, c, jb, i);
             const int j = i + s.off[o];
             // j's predecessor is i (j - i = o; only interior nodes carry one).
             // One parent per child, so one writer; the NaN test skips
             // children the pull already resolved.
             if (s.ival[j] == o && isnan(s.val[j])) {
-              s.val[j] = __dadd_rn(vi, Wi[(s.cls[j] & kClassMask) * n_off + o]);
+              s.val[j] = __dadd_rn(
+                  vi, w_push(jb, WI, kFieldI, ki, s.cls[j] & kClassMask, o, n_off, gi));
               improved = true;
               jj = j;
             }
@@ -866,7 +929,8 @@ static int validate_job(const chert_trace_job& j, uint32_t outs) {
     return fail(CHERT_ERR_INVALID_ARG, "radius must be 1..8");
   if (!(g->hx > 0.0) || !(g->hz > 0.0) || !isfinite(g->hx) || !isfinite(g->hz))
     return fail(CHERT_ERR_INVALID_ARG, "spacing must be positive");
-  if (!g->class_id_dev) return fail(CHERT_ERR_INVALID_ARG, "null class ids");
+  if (!g->class_id_dev && j.n_classes != g->nx * g->nz)
+    return fail(CHERT_ERR_INVALID_ARG, "no class map: the cache must hold one class per node");
   if (j.mode < 0 || j.mode > 2 || !(j.d->mode_mask & (1u << j.mode)))
     return fail(CHERT_ERR_INVALID_ARG, "mode not in the cache");
   if (j.n_src < 1) return fail(CHERT_ERR_INVALID_ARG, "need at least one source");
@@ -880,8 +944,8 @@ static int validate_job(const chert_trace_job& j, uint32_t outs) {
       ((outs & CHERT_OUT_TSTAR) && !j.tstar_dev) || ((outs & CHERT_OUT_PRED_P) && !j.pred_p_dev) ||
       ((outs & CHERT_OUT_PRED_A) && !j.pred_a_dev))
     return fail(CHERT_ERR_INVALID_ARG, "a selected output is NULL");
-  if ((int64_t)j.n_classes * j.n_classes > ((int64_t)1 << 26))
-    return fail(CHERT_ERR_UNSUPPORTED, "class-pair table too large");
+  if (g->class_id_dev && (int64_t)j.n_classes * j.n_classes > ((int64_t)1 << 26))
+    return fail(CHERT_ERR_UNSUPPORTED, "class-pair table too large (use one class per node)");
   return CHERT_OK;
 }
 
@@ -934,8 +998,11 @@ static int make_plan(const chert_trace_job* jobs, int n_jobs, const chert_trace_
     P->n_tiles += (int64_t)np * ntx * ntz;
     prob_nodes += (int64_t)np * g->nx * g->nz;
     if (ntx + ntz > max_tile_span) max_tile_span = ntx + ntz;
-    size_t wf = (size_t)jobs[j].n_classes * jobs[j].n_classes * P->n_off * sizeof(double);
-    if (wf <= kWLdsBytes && (int)(wf / sizeof(double)) > w_lds) w_lds = (int)(wf / sizeof(double));
+    if (g->class_id_dev) {
+      size_t wf = (size_t)jobs[j].n_classes * jobs[j].n_classes * P->n_off * sizeof(double);
+      if (wf <= kWLdsBytes && (int)(wf / sizeof(double)) > w_lds)
+        w_lds = (int)(wf / sizeof(double));
+    }
   }
   if (P->n_tiles >= 0x7fffffffLL || P->n_prob > 65535)
     return fail(CHERT_ERR_UNSUPPORTED, "batch too large for one launch");
@@ -945,7 +1012,7 @@ static int make_plan(const chert_trace_job* jobs, int n_jobs, const chert_trace_
   P->off_star = off;
   off += align256((size_t)kMaxOffsets * 2 * sizeof(int32_t));
   P->off_lbin = off;
-  off += align256((size_t)n_jobs * kMaxOffsets * (sizeof(double) + sizeof(int32_t)));
+  off += align256((size_t)n_jobs * kMaxOffsets * (sizeof(double) + 2 * sizeof(int32_t)));
   P->off_jobs = off;
   off += align256((size_t)n_jobs * sizeof(JobDev));
   P->off_probs = off;
@@ -958,7 +1025,10 @@ static int make_plan(const chert_trace_job* jobs, int n_jobs, const chert_trace_
   off += 256;
   for (int j = 0; j < n_jobs; ++j) {
     P->off_W.push_back(off);
-    off += align256((size_t)2 * jobs[j].n_classes * jobs[j].n_classes * P->n_off * sizeof(double));
+    const size_t rows = jobs[j].g->class_id_dev
+                            ? (size_t)jobs[j].n_classes * jobs[j].n_classes
+                            : (size_t)jobs[j].g->nx * jobs[j].g->nz;
+    off += align256((size_t)2 * rows * P->n_off * sizeof(double));
   }
   P->off_hop = off;
   off += align256((size_t)prob_nodes * sizeof(int32_t));
@@ -1001,18 +1071,34 @@ static int trace_batch(const chert_trace_job* jobs, int n_jobs, const chert_trac
 
   // forward star (shared offsets) and per-job lengths/bins on the host
   std::vector<int32_t> star(2 * kMaxOffsets);
-  std::vector<uint8_t> lbin((size_t)n_jobs * kMaxOffsets * (sizeof(double) + sizeof(int32_t)));
+  std::vector<uint8_t> lbin((size_t)n_jobs * kMaxOffsets * (sizeof(double) + 2 * sizeof(int32_t)));
   double* hL = (double*)lbin.data();
   int32_t* hbin = (int32_t*)(hL + (size_t)n_jobs * kMaxOffsets);
+  int32_t* hcol = hbin + (size_t)n_jobs * kMaxOffsets;
   for (int j = 0; j < n_jobs; ++j) {
     const chert_grid* g = jobs[j].g;
-    star_2d(P.R, g->hx, g->hz, jobs[j].d->n_dirs, star.data(), star.data() + kMaxOffsets,
+    const chert_cache_desc* d = jobs[j].d;
+    star_2d(P.R, g->hx, g->hz, d->n_dirs, star.data(), star.data() + kMaxOffsets,
             hL + (size_t)j * kMaxOffsets, hbin + (size_t)j * kMaxOffsets);
+    // cache column of every offset's bin
+    for (int o = 0; o < P.n_off; ++o) {
+      const int b = hbin[(size_t)j * kMaxOffsets + o];
+      int c = b;
+      if (d->n_subset) {
+        c = -1;
+        for (int q = 0; q < d->n_subset; ++q)
+          if (d->subset_host[q] == b) c = q;
+      }
+      if (c < 0) return fail(CHERT_ERR_INVALID_ARG, "the cache lacks a direction of the star");
+      hcol[(size_t)j * kMaxOffsets + o] = c;
+    }
   }
   int32_t* dox = (int32_t*)(ws + P.off_star);
   int32_t* doz = dox + kMaxOffsets;
   double* dL = (double*)(ws + P.off_lbin);
   int32_t* dbin = (int32_t*)(dL + (size_t)n_jobs * kMaxOffsets);
+  int32_t* dcol = dbin + (size_t)n_jobs * kMaxOffsets;
+  (void)dbin;
 
   std::vector<JobDev> jd(n_jobs);
   std::vector<ProbDev> probs;
@@ -1026,9 +1112,10 @@ static int trace_batch(const chert_trace_job* jobs, int n_jobs, const chert_trac
     d.nz = (int)J.g->nz;
     d.ntx = P.ntx[j];
     d.ntz = P.ntz[j];
-    d.K = P.K[j];
+    d.per_node = J.g->class_id_dev ? 0 : 1;
+    d.K = d.per_node ? 1 : P.K[j];
     size_t wf = (size_t)d.K * d.K * P.n_off;
-    d.w_in_lds = (wf <= (size_t)P.w_lds_doubles) ? 1 : 0;
+    d.w_in_lds = (!d.per_node && wf <= (size_t)P.w_lds_doubles) ? 1 : 0;
     d.class_id = J.g->class_id_dev;
     d.W = (const double*)(ws + P.off_W[j]);
     const int64_t n = P.nodes[j];
@@ -1103,17 +1190,28 @@ static int trace_batch(const chert_trace_job* jobs, int n_jobs, const chert_trac
     chert_cache_layout_of(J.d, J.n_classes, &lay);
     const uint8_t* cache = (const uint8_t*)J.cache_dev;
     const int64_t K = J.n_classes;
-    const int64_t ent = 3 * K * (int64_t)J.d->n_dirs;
-    const int64_t mslice = (int64_t)J.mode * K * J.d->n_dirs;
+    const int n_cols = J.d->n_subset ? J.d->n_subset : J.d->n_dirs;
+    const int64_t ent = 3 * K * (int64_t)n_cols;
+    const int64_t mslice = (int64_t)J.mode * K * n_cols;
     const double* fields = (const double*)(cache + lay.fields_offset);
     const double* Vm = fields + CHERT_F_V * ent + mslice;
     const double* Am = fields + CHERT_F_A * ent + mslice;
     const int32_t* Sm = (const int32_t*)(cache + lay.status_offset) + mslice;
-    int64_t tw = 2 * K * K * P.n_off;
-    int64_t blocks = (tw + 255) / 256;
-    CHERT_LAUNCH("k_weights", k_weights, dim3((unsigned)(blocks > 65536 ? 65536 : blocks)), dim3(256),
-                       0, s, (double*)(ws + P.off_W[j]), (int)K, P.n_off, Vm, Am, Sm,
-                       J.d->n_dirs, dL + (size_t)j * kMaxOffsets, dbin + (size_t)j * kMaxOffsets);
+    if (jd[j].per_node) {
+      int64_t tw = P.nodes[j] * P.n_off;
+      int64_t blocks = (tw + 255) / 256;
+      CHERT_LAUNCH("k_weights_node", k_weights_node,
+                   dim3((unsigned)(blocks > 65536 ? 65536 : blocks)), dim3(256), 0, s,
+                   (double*)(ws + P.off_W[j]), jd[j].nx, jd[j].nz, P.n_off, dox, doz,
+                   dL + (size_t)j * kMaxOffsets, dcol + (size_t)j * kMaxOffsets, n_cols, Vm,
+                   Am, Sm);
+    } else {
+      int64_t tw = 2 * K * K * P.n_off;
+      int64_t blocks = (tw + 255) / 256;
+      CHERT_LAUNCH("k_weights", k_weights, dim3((unsigned)(blocks > 65536 ? 65536 : blocks)),
+                   dim3(256), 0, s, (double*)(ws + P.off_W[j]), (int)K, P.n_off, Vm, Am, Sm,
+                   n_cols, dL + (size_t)j * kMaxOffsets, dcol + (size_t)j * kMaxOffsets);
+    }
   }
   int64_t max_nodes = 0;
   for (int64_t n : P.nodes) max_nodes = n > max_nodes ? n : max_nodes;

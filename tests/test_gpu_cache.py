@@ -148,3 +148,40 @@ def test_cache_invalid_class_flags_nonphys(G):
     fg, sg, fo, so = run_pair(G, np.stack([c, bad]), modes=(0,))
     assert np.all(sg[0, 1] == O.ST_NONPHYS)
     assert np.all(np.isnan(fg[0, 0, 1]))
+
+
+def test_cache_star_subset_columns(G, rock_table):
+    """Subset caches (the star's directions only) match the oracle's."""
+    import paper_2609_26108_amd as C
+    r = rock_table[2]
+    cls = np.stack([O.class_from_moduli(*(r[:5] * KM2), *r[5:10], tilt=0.4),
+                    O.class_from_thomsen(3000.0, 1732.0, 2300, 0.2, 0.1, 0.15, -0.2, 0, 60, 40)])
+    sub = C.star_subset(5, 5.0, 5.0)
+    desc = C.cache_desc(modes=(0, 1, 2), subset=sub)
+    cache = G.build_cache(G.classes_from_arrays(cls), desc)
+    fg, sg = G.cache_to_numpy(cache, desc, 2)
+    fo, so = O.build_cache_2d(cls, subset=sub)
+    compare_cache(fg, sg, fo, so, (0, 1, 2))
+
+
+def test_cache_per_node_fused_path(G):
+    """One class per node of a small complex model (>= 512 jobs, so the fused
+    sweep-in-LDS launch runs), star subset, qSV; classes converted on the
+    device (chert_classes_from_thomsen) and by the oracle."""
+    import paper_2609_26108_amd as C
+    m = W.complex_2d(nx=26, nz=21, h=10.0, water_m=40.0, n_layers=6, n_faults=1, seed=3,
+                     radius=3)
+    rows = m.param_rows()
+    params = torch.from_numpy(rows).to(G.DEV)
+    classes = torch.empty((rows.shape[0], 13), dtype=torch.float64, device=G.DEV)
+    C.chert_classes_from_thomsen(params, classes)
+    cls_o = np.stack([O.class_from_thomsen(*r) for r in rows])
+    torch.cuda.synchronize()
+    assert np.array_equal(classes.cpu().numpy(), cls_o)
+    sub = C.star_subset(3, m.hx, m.hz)
+    desc = C.cache_desc(modes=(1,), n_sweep=720, subset=sub)
+    cache = G.build_cache(classes, desc)
+    fg, sg = G.cache_to_numpy(cache, desc, rows.shape[0])
+    fo, so = O.build_cache_2d(cls_o, mode_mask=0b010, n_sweep=720, subset=sub)
+    st = compare_cache(fg, sg, fo, so, (1,))
+    print("per-node", st)

@@ -196,3 +196,39 @@ def test_batch_uneven_grids_modes_sources_bitwise(G):
             o = O.trace_2d(mdl.nx, mdl.nz, mdl.hx, mdl.hz, mdl.class_id, mdl.radius,
                            f[0, mode], f[1, mode], s[mode], src)
             assert_fields_equal(g, o, si)
+
+
+def test_per_node_trace_bitwise(G):
+    """Per-node cache (no class map): GPU traveltimes and predecessors on an
+    imported oracle cache are bitwise the oracle's."""
+    import torch
+    Cm = C()
+    m = W.complex_2d(nx=45, nz=33, h=10.0, water_m=60.0, n_layers=8, n_faults=2, seed=5,
+                     radius=3, modes=(0, 1))
+    rows = m.param_rows()
+    cls = np.stack([O.class_from_thomsen(*r) for r in rows])
+    sub = O.star_subset(3, m.hx, m.hz)
+    f, s = O.build_cache_2d(cls, mode_mask=0b011, n_sweep=360, subset=sub)
+    desc = Cm.cache_desc(modes=(0, 1), n_sweep=360, subset=sub)
+    N = rows.shape[0]
+    cache = G.import_cache(f, s, desc, N)
+    for mode in (0, 1):
+        n = m.n_nodes
+        out = dict(tau_r=torch.empty((1, n), dtype=torch.float64, device=G.DEV),
+                   tau_i=torch.empty((1, n), dtype=torch.float64, device=G.DEV),
+                   tstar=torch.empty((1, n), dtype=torch.float64, device=G.DEV),
+                   pred_p=torch.empty((1, n), dtype=torch.int32, device=G.DEV),
+                   pred_a=torch.empty((1, n), dtype=torch.int32, device=G.DEV))
+        grid = Cm.make_grid(m.nx, m.nz, m.hx, m.hz, m.radius, None)
+        opts = Cm.trace_opts(Cm.OUT_ALL)
+        ws = torch.empty(Cm.chert_trace_workspace_bytes(desc, N, grid, 1, opts),
+                         dtype=torch.uint8, device=G.DEV)
+        Cm.chert_trace_field(desc, cache, N, grid, mode, m.sources, opts, workspace_dev=ws, **out)
+        torch.cuda.synchronize()
+        g = {"tauR": out["tau_r"].cpu().numpy(), "tauI": out["tau_i"].cpu().numpy(),
+             "tstar": out["tstar"].cpu().numpy(), "predP": out["pred_p"].cpu().numpy(),
+             "predA": out["pred_a"].cpu().numpy()}
+        o = O.trace_2d(m.nx, m.nz, m.hx, m.hz, None, m.radius, f[0, mode], f[1, mode], s[mode],
+                       m.sources[0], subset=sub)
+        print(f"mode {mode}: finite {int(np.isfinite(o['tauR']).sum())}", flush=True)
+        assert_fields_equal(g, o, 0)

@@ -391,3 +391,32 @@ def test_zero_weight_ties_use_min_hop_then_offset():
         ox, oz = offs[k]
         assert r["predA"][j] == (jx - ox) + nx * (jz - oz)
     _check_tree(nx, nz, R, 5.0, 5.0, cid, V, A, r["tauI"], r["predA"], r["hopA"], src, 1)
+
+
+def test_subset_cache_equals_full_cache_columns(rock_table):
+    """A cache restricted to the star's directions stores exactly the full
+    cache's values in those columns (same solve, different storage)."""
+    r = rock_table[0]
+    cls = np.stack([O.class_from_moduli(*(r[:5] * 1e6), *r[5:10], tilt=0.3),
+                    O.class_from_thomsen(3000.0, 1732.0, 2300, 0.2, 0.1, 0.15, -0.2, 0, 60, 40)])
+    sub = O.star_subset(3, 10.0, 10.0)
+    f, s = O.build_cache_2d(cls, mode_mask=0b011, n_sweep=360)
+    fs, ss = O.build_cache_2d(cls, mode_mask=0b011, n_sweep=360, subset=sub)
+    for m in (0, 1):
+        assert np.array_equal(fs[:, m], f[:, m][:, :, sub], equal_nan=True)
+        assert np.array_equal(ss[m], s[m][:, sub])
+
+
+def test_per_node_trace_equals_class_trace():
+    """One class per node (no class map) with the star subset gives bitwise
+    the traveltimes of the class-map form."""
+    rng = np.random.default_rng(31)
+    nx, nz, R, K = 14, 9, 3, 3
+    V, A, st = random_cache(K, rng)
+    cid = rng.integers(0, K, nx * nz).astype(np.int32)
+    sub = O.star_subset(R, 5.0, 5.0)
+    Vn, An, sn = V[cid][:, sub], A[cid][:, sub], st[cid][:, sub]
+    a = O.trace_2d(nx, nz, 5.0, 5.0, cid, R, V, A, st, 17)
+    b = O.trace_2d(nx, nz, 5.0, 5.0, None, R, Vn, An, sn, 17, subset=sub)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k

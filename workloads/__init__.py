@@ -125,3 +125,103 @@ def small_layered(nx=37, nz=23, h=10.0, n_layers=3, seed=7, radius=3, tilt_max=4
     src = [int(rng.integers(0, nx)) + nx * int(rng.integers(0, 3))]
     return Model2D(f"small_layered_{nx}x{nz}", nx, nz, h, h, layers, cid, src,
                    (QP, QSV, QSH), radius)
+
+
+@dataclass
+class PerNodeModel:
+    """Per-node Thomsen parameters (arrays [nz, nx]) on a regular grid."""
+    name: str
+    nx: int
+    nz: int
+    hx: float
+    hz: float
+    params: dict                 # vp0, vs0, rho, eps, delta, gamma, tilt, qp, qs
+    sources: List[int]
+    modes: tuple
+    radius: int
+    n_dirs: int = 360
+
+    @property
+    def n_nodes(self):
+        return self.nx * self.nz
+
+    def param_rows(self):
+        """[n_nodes, 10] rows (vp0, vs0, rho, eps, delta, gamma, tilt,
+        azimuth, qp, qs), node order ix + nx * iz."""
+        p = self.params
+        cols = [p["vp0"], p["vs0"], p["rho"], p["eps"], p["delta"], p["gamma"],
+                p["tilt"], np.zeros_like(p["vp0"]), p["qp"], p["qs"]]
+        return np.stack([c.reshape(-1) for c in cols], axis=1).astype(np.float64)
+
+    def layers(self):
+        return [Layer(*(float(v) for v in (r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[8], r[9])))
+                for r in self.param_rows()]
+
+
+def _smooth_field(rng, nz, nx, h, corr, lo, hi):
+    """Gaussian random field with correlation length ~corr (m), mapped to
+    [lo, hi] through its empirical range."""
+    kz = np.fft.fftfreq(nz, d=h)[:, None]
+    kx = np.fft.rfftfreq(nx, d=h)[None, :]
+    spec = np.exp(-0.5 * (2 * math.pi * corr) ** 2 * (kx ** 2 + kz ** 2) / 4.0)
+    noise = rng.standard_normal((nz, nx))
+    f = np.fft.irfft2(np.fft.rfft2(noise) * spec, s=(nz, nx))
+    f = (f - f.min()) / max(f.max() - f.min(), 1e-30)
+    return lo + (hi - lo) * f
+
+
+def complex_2d(nx=1701, nz=351, h=10.0, seed=None, n_layers=30, n_faults=5,
+               water_m=200.0, modes=(QSV,), radius=5, src_ix=None):
+    """Structurally complex 2D TTI + Q model with per-node parameters: about
+    30 folded layers cut by normal faults, Vp 1500-4700 m/s increasing with
+    depth (+-10 % per layer), an isotropic water layer (Q = 1000), smooth
+    eps/delta/gamma fields, tilt = local layer dip, Qp 20-200 log-linear in
+    depth, Qs = 0.6 Qp."""
+    rng = np.random.default_rng(seed_for(3) if seed is None else seed)
+    x = np.arange(nx) * h
+    z = np.arange(nz) * h
+    X, Z = np.meshgrid(x, z)
+    depth = (nz - 1) * h
+    # folded interfaces: base depths + two sines
+    base = np.sort(rng.uniform(water_m + 20.0, depth, n_layers))
+    horizons = []
+    for b in base:
+        a1, a2 = rng.uniform(0, 150, 2)
+        l1, l2 = rng.uniform(2000, 8000, 2)
+        p1, p2 = rng.uniform(0, 2 * math.pi, 2)
+        horizons.append(b + a1 * np.sin(2 * math.pi * x / l1 + p1) + a2 * np.sin(2 * math.pi * x / l2 + p2))
+    horizons = np.array(horizons)                     # [L, nx]
+    # normal faults: planes x = x0 + (z - z0) / tan(dip); hanging wall shifted
+    shift = np.zeros((nz, nx))
+    for _ in range(n_faults):
+        x0 = rng.uniform(0.1, 0.9) * x[-1]
+        dip = math.radians(rng.uniform(55, 70))
+        throw = rng.uniform(30, 150)
+        hanging = X > x0 + Z / math.tan(dip)
+        shift += np.where(hanging, throw, 0.0)
+    zz = Z - shift                                     # depth in the unfaulted frame
+    layer = (zz[None, :, :] > horizons[:, None, :]).sum(axis=0)
+    # local dip from the nearest horizon slope
+    slope = np.gradient(horizons, h, axis=1)           # [L, nx]
+    li = np.clip(layer - 1, 0, n_layers - 1)
+    dip = np.arctan(np.take_along_axis(slope, li, axis=0)) if n_layers else np.zeros((nz, nx))
+    vfac = 1.0 + rng.uniform(-0.1, 0.1, n_layers + 1)
+    vp = (1600.0 + (4700.0 - 1600.0) * np.clip(zz / depth, 0, 1)) * vfac[layer]
+    vp = np.clip(vp, 1500.0, 4700.0)
+    vs = vp / 1.9
+    rho = 1700.0 + 0.2 * vp
+    eps = _smooth_field(rng, nz, nx, h, 500.0, 0.0, 0.25)
+    delta = _smooth_field(rng, nz, nx, h, 500.0, -0.05, 0.15)
+    gamma = _smooth_field(rng, nz, nx, h, 500.0, 0.0, 0.15)
+    qp = np.exp(np.log(20.0) + (np.log(200.0) - np.log(20.0)) * np.clip(Z / depth, 0, 1))
+    qs = 0.6 * qp
+    water = Z < water_m
+    for a, v in ((vp, 1500.0), (vs, 0.0), (rho, 1000.0), (eps, 0.0), (delta, 0.0),
+                 (gamma, 0.0), (dip, 0.0), (qp, 1000.0), (qs, 1000.0)):
+        a[water] = v
+    params = dict(vp0=vp, vs0=vs, rho=rho, eps=eps, delta=delta, gamma=gamma, tilt=dip,
+                  qp=qp, qs=qs)
+    iz_src = min(int(water_m / h), nz - 1)
+    ix = nx // 2 if src_ix is None else src_ix
+    return PerNodeModel(f"complex2d_{nx}x{nz}", nx, nz, h, h, params, [ix + nx * iz_src],
+                        tuple(modes), radius)
