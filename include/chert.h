@@ -289,6 +289,127 @@ int chert_extract_raypath(const int32_t *pred_host, int64_t n_nodes,
 int chert_star_2d(int32_t radius, double hx, double hz, int32_t n_dirs,
                   int32_t *ox, int32_t *oz, double *len, int32_t *bin);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the cache solve (an addition to the paper's method,
+ * which finds coarse property classes too crude for structurally complex
+ * media and per-node caches too costly to solve; see its application to a
+ * Marmousi-type model and its conclusions).  An MLP maps
+ *   inputs  (16): a11/a33 - 1, a13/a33, a44/a33, a66/a33, 1/q11, 1/q13,
+ *                 1/q33, 1/q44, 1/q66 (0 when elastic), mode one-hot (3),
+ *                 cos psi, sin psi, cos 2 psi, sin 2 psi, psi = target ray
+ *                 angle in the symmetry-axis frame (eq 36);
+ *   outputs (4):  theta_R - psi (wrapped to (-pi, pi]), theta_I,
+ *                 log(V / sqrt(a33)), A sqrt(a33)   (eqs 9-11)
+ * through three tanh layers of 128 (linear output), standardised inputs and
+ * outputs.  Products run on BF16 operands with FP32 accumulation; master
+ * weights and Adam moments are FP32.  Parameter order (FP32): W1[16][128],
+ * b1[128], W2[128][128], b2, W3[128][128], b3, W4[128][4], b4[4]; a layer
+ * maps x -> x W + b.
+ *
+ * The surrogate lives in one caller-allocated device blob of total_bytes
+ * (256-byte aligned).  Layout (byte offsets from chert_surrogate_layout_of):
+ *   [0, 256)        header: uint32 magic 'CHSG' (0x47534843), version 1,
+ *                   n_in, n_hidden, n_out, n_params, int32 last Adam step
+ *   norm_offset     float in_mean[16], in_inv_std[16], out_mean[4],
+ *                   out_std[4]
+ *   params_offset   float params[n_params] (master weights)
+ *   adam_m_offset   float m[n_params];  adam_v_offset float v[n_params]
+ *   then BF16 operand copies of the weights (internal).
+ * Training data comes from solved caches (chert_surrogate_dataset); the
+ * cache builder then uses the surrogate as the starting point of its
+ * Newton polish (chert_build_cache_surrogate).
+ * ------------------------------------------------------------------------ */
+typedef struct chert_surrogate_layout {
+  size_t total_bytes;
+  size_t norm_offset;
+  size_t params_offset;
+  size_t adam_m_offset;
+  size_t adam_v_offset;
+  int32_t n_params; /* 35716 */
+  int32_t n_in;     /* 16 */
+  int32_t n_hidden; /* 128 */
+  int32_t n_out;    /* 4 */
+} chert_surrogate_layout;
+
+int chert_surrogate_layout_of(chert_surrogate_layout *out);
+
+/* Initialise a blob: master weights from params_dev (device, n_params
+ * floats, e.g. a seeded random draw), zero Adam moments, identity
+ * standardisation.  Asynchronous on `stream`. */
+int chert_surrogate_init(void *blob_dev, const float *params_dev, void *stream);
+
+/* Training samples of every (mode in d->mode_mask ascending, class, column)
+ * entry of a cache built with desc d, in that order (column fastest):
+ * x_dev [n][16] inputs, y_dev [n][4] targets, ok_dev [n] 1 where the entry's
+ * status is CHERT_ST_OK (others hold NaN or are unusable).  n = modes *
+ * n_classes * columns. */
+int chert_surrogate_dataset(const chert_cache_desc *d, const void *cache_dev,
+                            const chert_class *classes_dev, int64_t n_classes,
+                            float *x_dev, float *y_dev, int32_t *ok_dev,
+                            void *stream);
+
+/* Set the blob's standardisation to the mean and standard deviation
+ * (population; 1 where zero) of every input and target column over the n
+ * samples with ok_dev != 0. */
+int chert_surrogate_fit_norm(void *blob_dev, const float *x_dev,
+                             const float *y_dev, const int32_t *ok_dev,
+                             int64_t n, void *stream);
+
+/* Gradient of the mean squared error of the standardised outputs over the
+ * batch idx_dev[0..batch) (indices into x_dev / y_dev):
+ *   loss = sum over samples and outputs of (out - y_std)^2 / (4 batch).
+ * grad_dev: n_params floats (parameter order above); loss_dev: one float,
+ * nullable.  The sum over samples is taken per 32-sample tile and then over
+ * tiles in order, so the result does not depend on scheduling. */
+size_t chert_surrogate_grad_workspace_bytes(int32_t batch);
+int chert_surrogate_grad(const void *blob_dev, const float *x_dev,
+                         const float *y_dev, const int32_t *idx_dev,
+                         int32_t batch, float *grad_dev, float *loss_dev,
+                         void *workspace_dev, size_t workspace_bytes,
+                         void *stream);
+
+/* One Adam step (Kingma and Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8,
+ * bias-corrected, step counted from 1) on the master weights with gradient
+ * grad_dev; refreshes the BF16 copies. */
+int chert_surrogate_adam(void *blob_dev, const float *grad_dev, int32_t step,
+                         float lr, void *stream);
+
+/* Outputs (de-standardised, [n][4]) for inputs x_dev [n][16]. */
+int chert_surrogate_infer(const void *blob_dev, const float *x_dev, int64_t n,
+                          float *y_dev, void *stream);
+
+/* Counters of a surrogate-started build (device int64[8]):
+ * [0] (mode, class) jobs, [1] jobs sent to the plain solver, [2] directions
+ * started from the surrogate, [3] of them near a fold of the ray-angle map,
+ * [4] Newton not converged, [5] slope of the ray-angle map too small,
+ * [6] theta_I not the root nearest 0, [7] residual or entry rejected. */
+enum { CHERT_WARM_NSTATS = 8 };
+
+/* Scratch needed by chert_build_cache_surrogate. */
+size_t chert_build_cache_surrogate_workspace_bytes(const chert_cache_desc *d,
+                                                   int64_t n_classes);
+
+/* Build the same cache as chert_build_cache, starting every direction's
+ * root search from the surrogate instead of a theta_R sweep:
+ *   1. the MLP predicts (theta_R, theta_I) for every solved direction;
+ *   2. an FP64 Newton iteration on (homogeneity residual, ray-direction
+ *      miss) (eq 9, eq 26's target direction) polishes it;
+ *   3. the root is accepted only if it is the one the plain search selects:
+ *      the elastic ray-angle map of the class has no fold (triplication)
+ *      within 2 degrees of the direction, the map's slope at the root is
+ *      at least 0.05, theta_I is the root of the residual nearest 0, and
+ *      the residual is at most resid_tol (0 = 1e-11);
+ *   4. every (mode, class) job with a rejected direction is solved again by
+ *      the plain path (sweep and brackets), so each entry equals the plain
+ *      solver's to the Newton tolerance.
+ * stats_dev: nullable device int64[CHERT_WARM_NSTATS], overwritten. */
+int chert_build_cache_surrogate(const chert_cache_desc *d,
+                                const chert_class *classes_dev,
+                                int64_t n_classes, const void *blob_dev,
+                                double resid_tol, void *cache_dev,
+                                int64_t *stats_dev, void *workspace_dev,
+                                size_t workspace_bytes, void *stream);
+
 /* Measurement support.  While enabled, every kernel launch the library
  * makes (or, if `only` is non-NULL, every launch of the kernel of that name)
  * is bracketed by HIP events on its stream; chert_prof_read() synchronises

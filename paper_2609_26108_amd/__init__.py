@@ -35,7 +35,14 @@ EXPORTS = (
     "chert_trace_batch_workspace_bytes", "chert_trace_batch",
     "chert_extract_raypath", "chert_star_2d", "chert_last_error",
     "chert_prof_enable", "chert_prof_read",
+    "chert_surrogate_layout_of", "chert_surrogate_init", "chert_surrogate_dataset",
+    "chert_surrogate_fit_norm", "chert_surrogate_grad_workspace_bytes", "chert_surrogate_grad",
+    "chert_surrogate_adam", "chert_surrogate_infer",
+    "chert_build_cache_surrogate_workspace_bytes", "chert_build_cache_surrogate",
 )
+WARM_NSTATS = 8
+WARM_STATS = ("jobs", "fallback_jobs", "directions", "fold", "newton_fail", "slope",
+              "theta_i_not_nearest", "rejected")
 
 
 class ChertError(RuntimeError):
@@ -105,6 +112,14 @@ class TraceOpts(ctypes.Structure):
                 ("stats_host", ctypes.c_void_p)]
 
 
+class SurrogateLayout(ctypes.Structure):
+    _fields_ = [("total_bytes", ctypes.c_size_t), ("norm_offset", ctypes.c_size_t),
+                ("params_offset", ctypes.c_size_t), ("adam_m_offset", ctypes.c_size_t),
+                ("adam_v_offset", ctypes.c_size_t), ("n_params", ctypes.c_int32),
+                ("n_in", ctypes.c_int32), ("n_hidden", ctypes.c_int32),
+                ("n_out", ctypes.c_int32)]
+
+
 class ProfEntry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int64),
                 ("total_ms", ctypes.c_double)]
@@ -144,6 +159,18 @@ def lib():
         L.chert_star_2d.argtypes = [i32, d, d, i32, P, P, P, P]
         L.chert_prof_enable.argtypes = [i32, ctypes.c_char_p]
         L.chert_prof_read.argtypes = [P, i32, P]
+        L.chert_surrogate_layout_of.argtypes = [P]
+        L.chert_surrogate_init.argtypes = [P, P, P]
+        L.chert_surrogate_dataset.argtypes = [P, P, P, i64, P, P, P, P]
+        L.chert_surrogate_fit_norm.argtypes = [P, P, P, P, i64, P]
+        L.chert_surrogate_grad_workspace_bytes.argtypes = [i32]
+        L.chert_surrogate_grad_workspace_bytes.restype = sz
+        L.chert_surrogate_grad.argtypes = [P, P, P, P, i32, P, P, P, sz, P]
+        L.chert_surrogate_adam.argtypes = [P, P, i32, ctypes.c_float, P]
+        L.chert_surrogate_infer.argtypes = [P, P, i64, P, P]
+        L.chert_build_cache_surrogate_workspace_bytes.argtypes = [P, i64]
+        L.chert_build_cache_surrogate_workspace_bytes.restype = sz
+        L.chert_build_cache_surrogate.argtypes = [P, P, i64, P, d, P, P, P, sz, P]
         _lib = L
     return _lib
 
@@ -342,6 +369,121 @@ def chert_trace_batch(batch, opts, workspace_dev, stream=None):
     ws = workspace_dev.numel() * workspace_dev.element_size() if workspace_dev is not None else 0
     _check(lib().chert_trace_batch(arr, n, ctypes.byref(opts), _ptr(workspace_dev), ws,
                                    _stream(stream)))
+
+
+# -------------------------------------------------------------- surrogate --
+
+def _nbytes(t):
+    return 0 if t is None else t.numel() * t.element_size()
+
+
+def chert_surrogate_layout_of():
+    out = SurrogateLayout()
+    _check(lib().chert_surrogate_layout_of(ctypes.byref(out)))
+    return out
+
+
+def chert_surrogate_init(blob_dev, params_dev, stream=None):
+    """blob_dev: uint8 device tensor of total_bytes (256-byte aligned);
+    params_dev: float32 device tensor [n_params]."""
+    _check(lib().chert_surrogate_init(_ptr(blob_dev), _ptr(params_dev), _stream(stream)))
+
+
+def chert_surrogate_dataset(desc, cache_dev, classes_dev, n_classes, x_dev, y_dev, ok_dev,
+                            stream=None):
+    """x_dev float32 [n, 16], y_dev float32 [n, 4], ok_dev int32 [n] with n =
+    modes * n_classes * columns."""
+    _check(lib().chert_surrogate_dataset(ctypes.byref(desc), _ptr(cache_dev), _ptr(classes_dev),
+                                         n_classes, _ptr(x_dev), _ptr(y_dev), _ptr(ok_dev),
+                                         _stream(stream)))
+
+
+def chert_surrogate_fit_norm(blob_dev, x_dev, y_dev, ok_dev, stream=None):
+    _check(lib().chert_surrogate_fit_norm(_ptr(blob_dev), _ptr(x_dev), _ptr(y_dev), _ptr(ok_dev),
+                                          x_dev.shape[0], _stream(stream)))
+
+
+def chert_surrogate_grad_workspace_bytes(batch):
+    return lib().chert_surrogate_grad_workspace_bytes(batch)
+
+
+def chert_surrogate_grad(blob_dev, x_dev, y_dev, idx_dev, grad_dev, loss_dev, workspace_dev,
+                         stream=None):
+    """idx_dev int32 [batch]; grad_dev float32 [n_params]; loss_dev float32
+    [1] or None."""
+    _check(lib().chert_surrogate_grad(_ptr(blob_dev), _ptr(x_dev), _ptr(y_dev), _ptr(idx_dev),
+                                      idx_dev.numel(), _ptr(grad_dev), _ptr(loss_dev),
+                                      _ptr(workspace_dev), _nbytes(workspace_dev),
+                                      _stream(stream)))
+
+
+def chert_surrogate_adam(blob_dev, grad_dev, step, lr, stream=None):
+    _check(lib().chert_surrogate_adam(_ptr(blob_dev), _ptr(grad_dev), int(step), float(lr),
+                                      _stream(stream)))
+
+
+def chert_surrogate_infer(blob_dev, x_dev, y_dev, stream=None):
+    _check(lib().chert_surrogate_infer(_ptr(blob_dev), _ptr(x_dev), x_dev.shape[0], _ptr(y_dev),
+                                       _stream(stream)))
+
+
+def chert_build_cache_surrogate_workspace_bytes(desc, n_classes):
+    return lib().chert_build_cache_surrogate_workspace_bytes(ctypes.byref(desc), n_classes)
+
+
+def chert_build_cache_surrogate(desc, classes_dev, n_classes, blob_dev, cache_dev, workspace_dev,
+                                stats_dev=None, resid_tol=0.0, stream=None):
+    """stats_dev: int64 device tensor [WARM_NSTATS] or None."""
+    _check(lib().chert_build_cache_surrogate(ctypes.byref(desc), _ptr(classes_dev), n_classes,
+                                             _ptr(blob_dev), float(resid_tol), _ptr(cache_dev),
+                                             _ptr(stats_dev), _ptr(workspace_dev),
+                                             _nbytes(workspace_dev), _stream(stream)))
+
+
+def train_surrogate(blob_dev, x_dev, y_dev, ok_dev, steps, batch=2048, lr=2e-3, lr_end=2e-5,
+                    seed=0, stream=None):
+    """Minibatch Adam on the usable samples (ok_dev != 0): each epoch visits
+    them in a fresh seeded permutation; the learning rate decays from lr to
+    lr_end on a cosine.  Every step is one chert_surrogate_grad and one
+    chert_surrogate_adam call; returns the per-step losses (device
+    float32 tensor [steps]).  Starts from the blob's current weights and
+    continues its Adam moments at step 1 (a fresh chert_surrogate_init
+    resets them)."""
+    import math
+    t = _torch()
+    valid = np.flatnonzero(ok_dev.cpu().numpy()).astype(np.int32)
+    if valid.size == 0:
+        raise ChertError(1, "no usable samples")
+    batch = int(min(batch, valid.size))
+    rng = np.random.default_rng(seed)
+    dev = x_dev.device
+    grad = t.empty(chert_surrogate_layout_of().n_params, dtype=t.float32, device=dev)
+    losses = t.zeros(steps, dtype=t.float32, device=dev)
+    ws = t.empty(chert_surrogate_grad_workspace_bytes(batch), dtype=t.uint8, device=dev)
+    per_epoch = valid.size // batch
+    perm = None
+    for s in range(steps):
+        e, b = divmod(s, per_epoch)
+        if b == 0:
+            perm = t.from_numpy(rng.permutation(valid)).to(dev)
+        idx = perm[b * batch:(b + 1) * batch]
+        chert_surrogate_grad(blob_dev, x_dev, y_dev, idx, grad, losses[s:s + 1], ws, stream)
+        rate = lr_end + 0.5 * (lr - lr_end) * (1.0 + math.cos(math.pi * s / max(steps - 1, 1)))
+        chert_surrogate_adam(blob_dev, grad, s + 1, rate, stream)
+    return losses
+
+
+def surrogate_views(blob_dev):
+    """(params, adam_m, adam_v, norm[40]) float32 views into a blob tensor,
+    following the documented layout."""
+    lay = chert_surrogate_layout_of()
+    t = _torch()
+    n = lay.n_params
+
+    def v(off, k):
+        return blob_dev[off: off + 4 * k].view(dtype=t.float32)
+    return (v(lay.params_offset, n), v(lay.adam_m_offset, n), v(lay.adam_v_offset, n),
+            v(lay.norm_offset, 40))
 
 
 # ------------------------------------------------------------ cache views --

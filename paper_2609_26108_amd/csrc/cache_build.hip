@@ -16,6 +16,7 @@
 
 #include "chert.h"
 #include "chert_internal.h"
+#include "mlp.h"
 #include "physics.h"
 
 namespace chert {
@@ -343,44 +344,312 @@ __global__ void __launch_bounds__(64) k_solve(SolveArgs a) {
 // (mode, class) sweeps theta_R into LDS, then solves that class's
 // directions; no sweep table in HBM.
 constexpr int kNodeThreads = 256;
-__global__ void __launch_bounds__(kNodeThreads) k_build_fused(SolveArgs a) {
+__global__ void __launch_bounds__(kNodeThreads) k_build_fused(SolveArgs a, const int32_t* list,
+                                                              const int32_t* list_len,
+                                                              int64_t n_jobs) {
   extern __shared__ double2 tab[];
   __shared__ int s_br[kNodeThreads * kMaxBr];
+  const int64_t n = list ? (int64_t)*list_len : n_jobs;
+  for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
+    const int64_t job = list ? (int64_t)list[it] : it;
+    const int64_t k = job % a.n_classes;
+    const int mode = a.modes[job / a.n_classes];
+    const chert_class c = a.classes[k];
+    const int64_t row = ((int64_t)mode * a.n_classes + k) * a.n_cols;
+    const int32_t blocked = class_block(c, mode);
+    if (blocked) {
+      Entry none{};
+      none.V = NAN;
+      for (int sidx = threadIdx.x; sidx < a.n_solve; sidx += blockDim.x) {
+        int d, col, pcol;
+        dir_cols(a, sidx, &d, &col, &pcol);
+        store_pair(a, row, col, pcol, none, 0.0, blocked);
+      }
+      continue;  // block-uniform
+    }
+    const Medium m = load_medium(c);
+    __syncthreads();  // the previous job's solves are done with tab
+    for (int j = threadIdx.x; j < a.n_sweep; j += blockDim.x) {
+      const double thR = (j + 0.5) * (kTwoPi / a.n_sweep);
+      double thI;
+      double2 out = make_double2(0.0, NAN);
+      if (theta_imag(m, mode, a.kernel, thR, &thI)) {
+        const double psi = ray_angle(energy_velocity(m, mode, a.kernel, thR, thI));
+        if (isfinite(psi)) out = make_double2(thI, psi);
+      }
+      tab[j] = out;
+    }
+    __syncthreads();
+    for (int sidx = threadIdx.x; sidx < a.n_solve; sidx += blockDim.x) {
+      int d, col, pcol;
+      dir_cols(a, sidx, &d, &col, &pcol);
+      Entry best{};
+      const int32_t st = solve_dir(a, m, mode, tab, d, s_br + threadIdx.x * kMaxBr, &best);
+      store_pair(a, row, col, pcol, best, m.tilt, st);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- warm start
+// Surrogate-started solve: the MLP (mlp.h) predicts (theta_R, theta_I) for
+// each solved direction, an FP64 Newton iteration polishes it, and the root
+// is kept only where it is provably the one the sweep-and-bracket search
+// above would pick; other jobs go back to k_build_fused.
+
+constexpr int kProxyN = 180;                        // elastic map samples on [0, pi)
+constexpr double kFoldSlope = 0.2;                  // d psi / d theta_R below this: fold
+constexpr double kFoldMargin = 2.0 * kPi / 180.0;   // guard band around a fold
+constexpr int kFoldBins = 720;                      // 0.5-degree ray-angle bins
+constexpr int kFoldWords = (kFoldBins + 31) / 32;
+constexpr double kWarmSlope = 0.05;                 // accepted roots: slope at least this
+constexpr double kWarmWindow = 0.35;                // Newton may move theta_R this far [rad]
+
+struct WarmArgs {
+  SolveArgs so;
+  const void* blob;
+  float2* pred;                 // [jobs][n_solve] (theta_R - psi, theta_I)
+  int32_t* fb_list;             // jobs for the plain path
+  int32_t* fb_len;
+  unsigned long long* stats;    // CHERT_WARM_NSTATS counters
+  double resid_tol;
+};
+
+__device__ __forceinline__ double dir_psi(const SolveArgs& a, int d, double tilt) {
+  return wrap_pi(d * (kTwoPi / a.n_dirs) - tilt);
+}
+
+// surrogate predictions for every (job, solved direction): 32 per workgroup
+__global__ void __launch_bounds__(mlp::kThreads) k_warm_predict(WarmArgs w, int64_t n_rows) {
+  __shared__ mlp::InferTile t;
+  const SolveArgs& a = w.so;
+  const mlp::Net n = mlp::net_of(w.blob);
+  const int64_t base = (int64_t)blockIdx.x * mlp::kRows;
+  __shared__ float s_f[mlp::kRows][mlp::kIn];
+  if (threadIdx.x < mlp::kRows) {
+    const int64_t e = base + threadIdx.x;
+    if (e < n_rows) {
+      const int64_t job = e / a.n_solve;
+      const int sidx = (int)(e % a.n_solve);
+      const chert_class c = a.classes[job % a.n_classes];
+      int d, col, pcol;
+      dir_cols(a, sidx, &d, &col, &pcol);
+      mlp::features(c, a.modes[job / a.n_classes], dir_psi(a, d, c.tilt), s_f[threadIdx.x]);
+    } else {
+      for (int i = 0; i < mlp::kIn; ++i) s_f[threadIdx.x][i] = NAN;
+    }
+  }
+  __syncthreads();
+  mlp::stage_x<false>(n, t.x, nullptr, [&](int r, int i) -> float { return s_f[r][i]; });
+  __syncthreads();
+  mlp::forward_infer(n, t, [&](int r, int col, float v) {
+    if (col < 2 && base + r < n_rows) (&w.pred[base + r].x)[col] = v;
+  });
+}
+
+// Newton on F = (h, psi - psi*) from (x0, y0), as newton_root but started
+// from a prediction and kept within kWarmWindow of it; *slope is
+// d psi / d theta_R along the homogeneous curve h = 0 at the last iterate.
+__device__ __forceinline__ bool warm_newton(const Medium& m, int mode, int kernel, bool el,
+                                         double psi_star, double x0, double y0, double* xo,
+                                         double* yo, double* slope) {
+  const double eps = 1e-7;
+  double x = x0, y = el ? 0.0 : y0, last = 1.0, sl = NAN;
+  for (int it = 0; it < 16; ++it) {
+    Vel v0 = energy_velocity(m, mode, kernel, x, y);
+    double F2 = wrap_pi(ray_angle(v0) - psi_star);
+    double dx, dy = 0.0;
+    if (el) {
+      Vel vx = energy_velocity(m, mode, kernel, x + eps, 0.0);
+      double dd = (wrap_pi(ray_angle(vx) - psi_star) - F2) / eps;
+      dx = -F2 / dd;
+      sl = dd;
+    } else {
+      double F1 = homog_residual(v0);
+      Vel vx = energy_velocity(m, mode, kernel, x + eps, y);
+      Vel vy = energy_velocity(m, mode, kernel, x, y + eps);
+      double J11 = (homog_residual(vx) - F1) / eps;
+      double J12 = (homog_residual(vy) - F1) / eps;
+      double J21 = (wrap_pi(ray_angle(vx) - psi_star) - F2) / eps;
+      double J22 = (wrap_pi(ray_angle(vy) - psi_star) - F2) / eps;
+      double det = J11 * J22 - J12 * J21;
+      dx = -(J22 * F1 - J12 * F2) / det;
+      dy = -(-J21 * F1 + J11 * F2) / det;
+      sl = -det / J12;
+    }
+    if (!isfinite(dx) || !isfinite(dy)) return false;
+    x += dx;
+    y += dy;
+    if (fabs(x - x0) > kWarmWindow || fabs(y) > 30.0 * kPi / 180.0) return false;
+    last = fmax(fabs(dx), fabs(dy));
+    if (last < 1e-15) break;
+  }
+  if (!(last < 1e-12)) return false;
+  *xo = x;
+  *yo = y;
+  *slope = sl;
+  return true;
+}
+
+// Is y the theta_I that theta_imag's outward scan returns at theta_R = x?
+// No bracket of the residual closer to 0 on either side, the bracket
+// holding y on its side, none in the same step on the other side.
+__device__ __forceinline__ bool thi_is_nearest(const Medium& m, int mode, int kernel, double x,
+                                               double y) {
+  const int kr = (int)floor(fabs(y) / kThiStep);
+  if (kr >= kThiSteps || y == 0.0) return false;
+  const double h0 = h_at(m, mode, kernel, x, 0.0);
+  if (h0 == 0.0) return false;
+  double hp_lo = h0, hn_hi = h0;
+  for (int k = 0; k <= kr; ++k) {
+    const double b = (k + 1) * kThiStep;
+    const double hp_hi = h_at(m, mode, kernel, x, b);
+    const double hn_lo = h_at(m, mode, kernel, x, -b);
+    const bool bp = brackets(hp_lo, hp_hi);
+    const bool bn = brackets(hn_lo, hn_hi);
+    if (k < kr) {
+      if (bp || bn) return false;
+    } else {
+      const bool mine = y > 0.0 ? bp : bn;
+      const bool other = y > 0.0 ? bn : bp;
+      if (!mine || other) return false;
+    }
+    hp_lo = hp_hi;
+    hn_hi = hn_lo;
+  }
+  return true;
+}
+
+__device__ __forceinline__ int fold_bin(double psi) {
+  int b = (int)floor((psi + kPi) * (kFoldBins / kTwoPi));
+  b %= kFoldBins;
+  return b < 0 ? b + kFoldBins : b;
+}
+
+// one wavefront per (mode, class) job
+__global__ void __launch_bounds__(64) k_warm_solve(WarmArgs w) {
+  __shared__ double s_psi[kProxyN];
+  __shared__ uint32_t s_fold[kFoldWords];
+  __shared__ uint32_t s_cnt[CHERT_WARM_NSTATS];
+  __shared__ int s_all;
+  const SolveArgs& a = w.so;
   const int64_t job = blockIdx.x;
+  const int lane = threadIdx.x;
   const int64_t k = job % a.n_classes;
   const int mode = a.modes[job / a.n_classes];
   const chert_class c = a.classes[k];
   const int64_t row = ((int64_t)mode * a.n_classes + k) * a.n_cols;
-  int32_t blocked = class_block(c, mode);
+  if (lane < CHERT_WARM_NSTATS) s_cnt[lane] = 0;
+  if (lane < kFoldWords) s_fold[lane] = 0;
+  if (lane == 0) s_all = 0;
+  const int32_t blocked = class_block(c, mode);
   if (blocked) {
     Entry none{};
     none.V = NAN;
-    for (int sidx = threadIdx.x; sidx < a.n_solve; sidx += blockDim.x) {
+    for (int sidx = lane; sidx < a.n_solve; sidx += 64) {
       int d, col, pcol;
       dir_cols(a, sidx, &d, &col, &pcol);
       store_pair(a, row, col, pcol, none, 0.0, blocked);
     }
+    if (lane == 0) atomicAdd(&w.stats[0], 1ull);
     return;  // block-uniform
   }
   const Medium m = load_medium(c);
-  for (int j = threadIdx.x; j < a.n_sweep; j += blockDim.x) {
-    const double thR = (j + 0.5) * (kTwoPi / a.n_sweep);
-    double thI;
-    double2 out = make_double2(0.0, NAN);
-    if (theta_imag(m, mode, a.kernel, thR, &thI)) {
-      const double psi = ray_angle(energy_velocity(m, mode, a.kernel, thR, thI));
-      if (isfinite(psi)) out = make_double2(thI, psi);
+  const bool el = theta_i_zero(m, mode);
+
+  // elastic stand-in of the ray-angle map psi(theta_R) on [0, pi) (the other
+  // half is its centrosymmetric image); folds and near-folds within the
+  // margin mark ray-angle bins where the map may have several branches
+  Medium me = m;
+  me.a11.im = me.a13.im = me.a33.im = me.a44.im = me.a66.im = 0.0;
+  me.elastic_ps = me.elastic_sh = true;
+  for (int j = lane; j < kProxyN; j += 64)
+    s_psi[j] = ray_angle(energy_velocity(me, mode, a.kernel, (j + 0.5) * (kPi / kProxyN), 0.0));
+  __syncthreads();
+  for (int j = lane; j < kProxyN; j += 64) {
+    const double pa = s_psi[j];
+    const double pb = j + 1 < kProxyN ? s_psi[j + 1] : s_psi[0] + kPi;
+    if (!isfinite(pa) || !isfinite(pb)) {
+      s_all = 1;
+      continue;
     }
-    tab[j] = out;
+    const double dp = wrap_pi(pb - pa);
+    if (dp * (kProxyN / kPi) >= kFoldSlope) continue;
+    const double lo = fmin(pa, pa + dp) - kFoldMargin;
+    const double hi = fmax(pa, pa + dp) + kFoldMargin;
+    const int nb = (int)floor((hi - lo) * (kFoldBins / kTwoPi)) + 2;
+    for (int half = 0; half < 2; ++half) {
+      const int b0 = fold_bin(lo + half * kPi);
+      for (int q = 0; q < nb && q < kFoldBins; ++q) {
+        const int b = (b0 + q) % kFoldBins;
+        atomicOr(&s_fold[b >> 5], 1u << (b & 31));
+      }
+    }
   }
   __syncthreads();
-  for (int sidx = threadIdx.x; sidx < a.n_solve; sidx += blockDim.x) {
+
+  bool reject = false;
+  for (int sidx = lane; sidx < a.n_solve; sidx += 64) {
     int d, col, pcol;
     dir_cols(a, sidx, &d, &col, &pcol);
-    Entry best{};
-    const int32_t st = solve_dir(a, m, mode, tab, d, s_br + threadIdx.x * kMaxBr, &best);
-    store_pair(a, row, col, pcol, best, m.tilt, st);
+    const double psi_star = dir_psi(a, d, m.tilt);
+    atomicAdd(&s_cnt[2], 1u);
+    const int fb = fold_bin(psi_star);
+    if (s_all || (s_fold[fb >> 5] >> (fb & 31)) & 1u) {
+      atomicAdd(&s_cnt[3], 1u);
+      reject = true;
+      continue;
+    }
+    const float2 p = w.pred[job * a.n_solve + sidx];
+    double x, y, slope;
+    if (!warm_newton(m, mode, a.kernel, el, psi_star, psi_star + (double)p.x, (double)p.y, &x,
+                     &y, &slope)) {
+      atomicAdd(&s_cnt[4], 1u);
+      reject = true;
+      continue;
+    }
+    if (!(slope >= kWarmSlope)) {
+      atomicAdd(&s_cnt[5], 1u);
+      reject = true;
+      continue;
+    }
+    if (!el && !thi_is_nearest(m, mode, a.kernel, x, y)) {
+      atomicAdd(&s_cnt[6], 1u);
+      reject = true;
+      continue;
+    }
+    x = fmod(x, kTwoPi);
+    if (x < 0.0) x += kTwoPi;
+    const Vel v = energy_velocity(m, mode, a.kernel, x, y);
+    Entry e;
+    ray_quantities(v, &e);
+    e.thR = x;
+    e.thI = y;
+    const double h = el ? 0.0 : homog_residual(v);
+    e.res = fmax(fabs(h), fabs(wrap_pi(ray_angle(v) - psi_star)));
+    if (!(e.res <= w.resid_tol) || !(e.V > 0.0) || !isfinite(e.V) || !(e.A >= 0.0)) {
+      atomicAdd(&s_cnt[7], 1u);
+      reject = true;
+      continue;
+    }
+    store_pair(a, row, col, pcol, e, m.tilt, CHERT_ST_OK);
   }
+  const bool any = __any(reject);
+  __syncthreads();
+  if (lane == 0) {
+    s_cnt[0] = 1;
+    if (any) {
+      s_cnt[1] = 1;
+      const int32_t pos = atomicAdd(w.fb_len, 1);
+      w.fb_list[pos] = (int32_t)job;
+    }
+  }
+  __syncthreads();
+  if (lane < CHERT_WARM_NSTATS && s_cnt[lane]) atomicAdd(&w.stats[lane], (unsigned long long)s_cnt[lane]);
+}
+
+__global__ void k_warm_zero(int32_t* fb_len, unsigned long long* stats) {
+  if (threadIdx.x == 0) *fb_len = 0;
+  if (threadIdx.x < CHERT_WARM_NSTATS) stats[threadIdx.x] = 0ull;
 }
 
 __global__ void k_write_header(uint8_t* cache, int32_t dim, int32_t n_dirs, uint32_t mask,
@@ -414,43 +683,22 @@ static int64_t n_jobs_of(const chert_cache_desc* d, int64_t n_classes) {
   return (int64_t)__builtin_popcount(d->mode_mask & 7u) * n_classes;
 }
 
-extern "C" size_t chert_build_cache_workspace_bytes(const chert_cache_desc* d,
-                                                    int64_t n_classes) {
-  if (!d || n_classes <= 0 || d->n_sweep <= 0) return 0;
-  if (n_jobs_of(d, n_classes) >= kFusedJobs) return 0;  // sweep table stays in LDS
-  return (size_t)n_jobs_of(d, n_classes) * (size_t)d->n_sweep * sizeof(double2);
-}
-
-extern "C" int chert_build_cache(const chert_cache_desc* d, const chert_class* classes_dev,
-                                 int64_t n_classes, void* cache_dev, void* workspace_dev,
-                                 size_t workspace_bytes, void* stream) {
-  chert_cache_layout lay;
-  int rc = chert_cache_layout_of(d, n_classes, &lay);
-  if (rc != CHERT_OK) return rc;
-  if (!classes_dev || !cache_dev) return fail(CHERT_ERR_INVALID_ARG, "null classes or cache");
-  if (d->n_sweep > kMaxSweep)
-    return fail(CHERT_ERR_INVALID_ARG, "n_sweep above the LDS table limit");
-  const size_t need = chert_build_cache_workspace_bytes(d, n_classes);
-  if (need > 0 && (!workspace_dev || workspace_bytes < need))
-    return fail(CHERT_ERR_INVALID_ARG, "workspace too small");
-  hipStream_t s = (hipStream_t)stream;
-  uint8_t* cache = (uint8_t*)cache_dev;
-
-  int modes[3], n_modes = 0;
-  for (int m = 0; m < 3; ++m)
-    if (d->mode_mask & (1u << m)) modes[n_modes++] = m;
-
+// Solve arguments of a build (desc already validated): modes, columns, the
+// solved directions and the columns of their centrosymmetric copies.
+static SolveArgs solve_args(const chert_cache_desc* d, const chert_class* classes_dev,
+                            int64_t n_classes, uint8_t* cache, const chert_cache_layout& lay,
+                            const void* table) {
   SolveArgs so{};
+  for (int m = 0; m < 3; ++m)
+    if (d->mode_mask & (1u << m)) so.modes[so.n_modes++] = m;
   so.classes = classes_dev;
   so.n_classes = n_classes;
-  so.n_modes = n_modes;
-  for (int i = 0; i < 3; ++i) so.modes[i] = i < n_modes ? modes[i] : 0;
   so.kernel = d->kernel;
   so.n_sweep = d->n_sweep;
   so.n_dirs = d->n_dirs;
-  so.table = (const double2*)workspace_dev;
-  so.fields = (double*)(cache + lay.fields_offset);
-  so.status = (int32_t*)(cache + lay.status_offset);
+  so.table = (const double2*)table;
+  so.fields = cache ? (double*)(cache + lay.fields_offset) : nullptr;
+  so.status = cache ? (int32_t*)(cache + lay.status_offset) : nullptr;
   const int half = d->n_dirs / 2;
   if (d->n_subset == 0) {
     so.subset = 0;
@@ -471,19 +719,59 @@ extern "C" int chert_build_cache(const chert_cache_desc* d, const chert_class* c
       ++so.n_solve;
     }
   }
+  return so;
+}
+
+static int common_checks(const chert_cache_desc* d, const chert_class* classes_dev,
+                         int64_t n_classes, const void* cache_dev, chert_cache_layout* lay) {
+  int rc = chert_cache_layout_of(d, n_classes, lay);
+  if (rc != CHERT_OK) return rc;
+  if (!classes_dev || !cache_dev) return fail(CHERT_ERR_INVALID_ARG, "null classes or cache");
+  if (d->n_sweep > kMaxSweep)
+    return fail(CHERT_ERR_INVALID_ARG, "n_sweep above the LDS table limit");
+  if (n_jobs_of(d, n_classes) > 0x7fffffffLL)
+    return fail(CHERT_ERR_INVALID_ARG, "too many classes");
+  return CHERT_OK;
+}
+
+static int launch_status() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+  return CHERT_OK;
+}
+
+extern "C" size_t chert_build_cache_workspace_bytes(const chert_cache_desc* d,
+                                                    int64_t n_classes) {
+  if (!d || n_classes <= 0 || d->n_sweep <= 0) return 0;
+  if (n_jobs_of(d, n_classes) >= kFusedJobs) return 0;  // sweep table stays in LDS
+  return (size_t)n_jobs_of(d, n_classes) * (size_t)d->n_sweep * sizeof(double2);
+}
+
+extern "C" int chert_build_cache(const chert_cache_desc* d, const chert_class* classes_dev,
+                                 int64_t n_classes, void* cache_dev, void* workspace_dev,
+                                 size_t workspace_bytes, void* stream) {
+  chert_cache_layout lay;
+  int rc = common_checks(d, classes_dev, n_classes, cache_dev, &lay);
+  if (rc != CHERT_OK) return rc;
+  const size_t need = chert_build_cache_workspace_bytes(d, n_classes);
+  if (need > 0 && (!workspace_dev || workspace_bytes < need))
+    return fail(CHERT_ERR_INVALID_ARG, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* cache = (uint8_t*)cache_dev;
+  const SolveArgs so = solve_args(d, classes_dev, n_classes, cache, lay, workspace_dev);
 
   CHERT_LAUNCH("k_write_header", k_write_header, dim3(1), dim3(64), 0, s, cache, d->dim,
                d->n_dirs, d->mode_mask, d->kernel, d->n_sweep, d->n_subset, n_classes);
-  const int64_t jobs = (int64_t)n_modes * n_classes;
-  if (jobs > 0x7fffffffLL) return fail(CHERT_ERR_INVALID_ARG, "too many classes");
+  const int64_t jobs = (int64_t)so.n_modes * n_classes;
   if (jobs >= kFusedJobs) {
     CHERT_LAUNCH("k_build_fused", k_build_fused, dim3((unsigned)jobs), dim3(kNodeThreads),
-                 (size_t)d->n_sweep * sizeof(double2), s, so);
+                 (size_t)d->n_sweep * sizeof(double2), s, so, (const int32_t*)nullptr,
+                 (const int32_t*)nullptr, jobs);
   } else if (jobs > 0) {
     SweepArgs sa{};
     sa.classes = classes_dev;
     sa.n_classes = n_classes;
-    sa.n_modes = n_modes;
+    sa.n_modes = so.n_modes;
     for (int i = 0; i < 3; ++i) sa.modes[i] = so.modes[i];
     sa.kernel = d->kernel;
     sa.n_sweep = d->n_sweep;
@@ -496,7 +784,64 @@ extern "C" int chert_build_cache(const chert_cache_desc* d, const chert_class* c
     CHERT_LAUNCH("k_solve", k_solve, dim3((unsigned)(jobs * chunks)), dim3(64),
                  (size_t)d->n_sweep * sizeof(double2), s, so);
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
-  return CHERT_OK;
+  return launch_status();
+}
+
+// workspace of the surrogate-started build: predictions, fallback job list,
+// its length and the internal counters
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+extern "C" size_t chert_build_cache_surrogate_workspace_bytes(const chert_cache_desc* d,
+                                                              int64_t n_classes) {
+  chert_cache_layout lay;
+  if (!d || n_classes <= 0 || chert_cache_layout_of(d, n_classes, &lay) != CHERT_OK) return 0;
+  const SolveArgs so = solve_args(d, nullptr, n_classes, nullptr, lay, nullptr);
+  const size_t jobs = (size_t)n_jobs_of(d, n_classes);
+  return al256(jobs * so.n_solve * sizeof(float2)) + al256(jobs * sizeof(int32_t)) + 256;
+}
+
+extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
+                                           const chert_class* classes_dev, int64_t n_classes,
+                                           const void* blob_dev, double resid_tol,
+                                           void* cache_dev, int64_t* stats_dev,
+                                           void* workspace_dev, size_t workspace_bytes,
+                                           void* stream) {
+  chert_cache_layout lay;
+  int rc = common_checks(d, classes_dev, n_classes, cache_dev, &lay);
+  if (rc != CHERT_OK) return rc;
+  if (!blob_dev || ((uintptr_t)blob_dev & 255u))
+    return fail(CHERT_ERR_INVALID_ARG, "null or unaligned surrogate blob");
+  if (!(resid_tol >= 0.0)) return fail(CHERT_ERR_INVALID_ARG, "negative residual tolerance");
+  const size_t need = chert_build_cache_surrogate_workspace_bytes(d, n_classes);
+  if (!workspace_dev || workspace_bytes < need)
+    return fail(CHERT_ERR_INVALID_ARG, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* cache = (uint8_t*)cache_dev;
+  WarmArgs w{};
+  w.so = solve_args(d, classes_dev, n_classes, cache, lay, nullptr);
+  const int64_t jobs = (int64_t)w.so.n_modes * n_classes;
+  const int64_t rows = jobs * w.so.n_solve;
+  uint8_t* ws = (uint8_t*)workspace_dev;
+  w.blob = blob_dev;
+  w.pred = (float2*)ws;
+  w.fb_list = (int32_t*)(ws + al256(rows * sizeof(float2)));
+  w.fb_len = (int32_t*)(ws + al256(rows * sizeof(float2)) + al256(jobs * sizeof(int32_t)));
+  w.stats = stats_dev ? (unsigned long long*)stats_dev : (unsigned long long*)(w.fb_len + 16);
+  w.resid_tol = resid_tol > 0.0 ? resid_tol : 1e-11;
+
+  CHERT_LAUNCH("k_write_header", k_write_header, dim3(1), dim3(64), 0, s, cache, d->dim,
+               d->n_dirs, d->mode_mask, d->kernel, d->n_sweep, d->n_subset, n_classes);
+  CHERT_LAUNCH("k_warm_zero", k_warm_zero, dim3(1), dim3(64), 0, s, w.fb_len, w.stats);
+  if (jobs > 0 && rows > 0) {
+    const int64_t blocks = (rows + mlp::kRows - 1) / mlp::kRows;
+    if (blocks > 0x7fffffffLL) return fail(CHERT_ERR_INVALID_ARG, "too many entries");
+    CHERT_LAUNCH("k_warm_predict", k_warm_predict, dim3((unsigned)blocks), dim3(mlp::kThreads),
+                 0, s, w, rows);
+    CHERT_LAUNCH("k_warm_solve", k_warm_solve, dim3((unsigned)jobs), dim3(64), 0, s, w);
+    const int64_t grid = jobs < 4096 ? jobs : 4096;
+    CHERT_LAUNCH("k_build_fused", k_build_fused, dim3((unsigned)grid), dim3(kNodeThreads),
+                 (size_t)d->n_sweep * sizeof(double2), s, w.so, (const int32_t*)w.fb_list,
+                 (const int32_t*)w.fb_len, jobs);
+  }
+  return launch_status();
 }

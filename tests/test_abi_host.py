@@ -152,3 +152,52 @@ def test_device_calls_validate_before_launch():
         C.chert_trace_field(d, _FakeTensor(), 3, g3, 0, [0], o, workspace_dev=_FakeTensor(), stream=0)
     assert e.value.code == 2
     assert C.chert_trace_workspace_bytes(d, 3, g, 1, o) > 0
+
+
+class _Ptr(_FakeTensor):
+    """A fake device pointer value (never dereferenced)."""
+    def __init__(self, addr, n=0, shape=(0,)):
+        super().__init__(n)
+        self.addr = addr
+        self.shape = shape
+
+    def data_ptr(self):
+        return self.addr
+
+
+def test_surrogate_layout_and_validation():
+    lay = C.chert_surrogate_layout_of()
+    assert (lay.n_params, lay.n_in, lay.n_hidden, lay.n_out) == (35716, 16, 128, 4)
+    for off in (lay.norm_offset, lay.params_offset, lay.adam_m_offset, lay.adam_v_offset,
+                lay.total_bytes):
+        assert off % 256 == 0
+    assert lay.adam_m_offset >= lay.params_offset + 4 * lay.n_params
+    assert lay.adam_v_offset >= lay.adam_m_offset + 4 * lay.n_params
+    assert lay.total_bytes > lay.adam_v_offset + 4 * lay.n_params
+    ok = _Ptr(0x10000)
+    for blob in (_FakeTensor(), _Ptr(0x10010)):  # null, unaligned
+        with pytest.raises(C.ChertError) as e:
+            C.chert_surrogate_init(blob, ok, stream=0)
+        assert e.value.code == 1
+    with pytest.raises(C.ChertError):  # null parameters
+        C.chert_surrogate_init(ok, _FakeTensor(), stream=0)
+    with pytest.raises(C.ChertError):  # step 0
+        C.chert_surrogate_adam(ok, ok, 0, 1e-3, stream=0)
+    with pytest.raises(C.ChertError):  # negative learning rate
+        C.chert_surrogate_adam(ok, ok, 1, -1.0, stream=0)
+    assert C.chert_surrogate_grad_workspace_bytes(0) == 0
+    assert C.chert_surrogate_grad_workspace_bytes(33) == 2 * C.chert_surrogate_grad_workspace_bytes(32)
+    idx = _Ptr(0x20000, n=64)
+    with pytest.raises(C.ChertError):  # workspace too small
+        C.chert_surrogate_grad(ok, ok, ok, idx, ok, None, _Ptr(0x30000, n=16), stream=0)
+    d = C.cache_desc(subset=C.star_subset(5, 10.0, 10.0), modes=(1,))
+    need = C.chert_build_cache_surrogate_workspace_bytes(d, 100)
+    assert need >= 100 * 40 // 2 * 8
+    with pytest.raises(C.ChertError):  # workspace too small
+        C.chert_build_cache_surrogate(d, ok, 100, ok, ok, _Ptr(0x40000, n=need - 1), stream=0)
+    with pytest.raises(C.ChertError):  # unaligned blob
+        C.chert_build_cache_surrogate(d, ok, 100, _Ptr(0x10010), ok, _Ptr(0x40000, n=need),
+                                      stream=0)
+    with pytest.raises(C.ChertError):  # negative residual tolerance
+        C.chert_build_cache_surrogate(d, ok, 100, ok, ok, _Ptr(0x40000, n=need),
+                                      resid_tol=-1.0, stream=0)

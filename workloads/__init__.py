@@ -225,3 +225,45 @@ def complex_2d(nx=1701, nz=351, h=10.0, seed=None, n_layers=30, n_faults=5,
     ix = nx // 2 if src_ix is None else src_ix
     return PerNodeModel(f"complex2d_{nx}x{nz}", nx, nz, h, h, params, [ix + nx * iz_src],
                         tuple(modes), radius)
+
+
+def surrogate_training_rows(n, seed=None):
+    """Thomsen rows [n, 10] (vp0, vs0, rho, eps, delta, gamma, tilt,
+    azimuth, qp, qs) spanning the media of the layered and the structurally
+    complex models: 45 % with Vs0 = Vp0 / 1.9 and the complex model's
+    anisotropy and Q ranges, 45 % with the layered model's ranges, 10 %
+    isotropic fluids (no shear, Q 1000); tilt uniform in [-90, 90) deg so
+    the local ray angles of a full direction set are covered densely."""
+    rng = np.random.default_rng(seed_for(6) if seed is None else seed)
+    rows = np.zeros((n, 10))
+    u = rng.random(n)
+    for i in range(n):
+        tilt = math.radians(rng.uniform(-90.0, 90.0))
+        if u[i] < 0.45:
+            vp = rng.uniform(1500.0, 4700.0)
+            qp = math.exp(rng.uniform(math.log(20.0), math.log(200.0)))
+            rows[i] = (vp, vp / 1.9, 1700.0 + 0.2 * vp, rng.uniform(0.0, 0.25),
+                       rng.uniform(-0.05, 0.15), rng.uniform(0.0, 0.15), tilt, 0.0, qp, 0.6 * qp)
+        elif u[i] < 0.9:
+            L = _layer_params(rng)
+            rows[i] = (L.vp0, L.vs0, L.rho, L.eps, L.delta, L.gamma, tilt, 0.0, L.qp, L.qs)
+        else:
+            vp = rng.uniform(1450.0, 1600.0)
+            rows[i] = (vp, 0.0, 1000.0, 0.0, 0.0, 0.0, tilt, 0.0, 1000.0, 1000.0)
+    return rows
+
+
+def mlp_init(shapes, seed=0):
+    """Initial parameters of a multilayer perceptron as one float32 vector:
+    weight matrices (2-D shapes, fan_in x fan_out) uniform in
+    +-sqrt(6 / (fan_in + fan_out)) (Glorot and Bengio 2010), biases zero,
+    concatenated in the order given."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shp in shapes:
+        if len(shp) == 2:
+            lim = math.sqrt(6.0 / (shp[0] + shp[1]))
+            parts.append(rng.uniform(-lim, lim, shp).reshape(-1))
+        else:
+            parts.append(np.zeros(shp).reshape(-1))
+    return np.concatenate(parts).astype(np.float32)
