@@ -77,6 +77,22 @@ def parse():
     p.add_argument("--tile", type=int, nargs=2, default=(0, 0), metavar=("TX", "TZ"),
                    help="relaxation tile shape (0 0 = library default)")
     p.add_argument("--push-group", type=int, default=0, help="offsets per push item (1, 2, 4)")
+    p.add_argument("--workload", choices=("layered", "complex2d"), default="layered",
+                   help="layered: the 5-layer model (default, the headline line); "
+                        "complex2d: per-node caches of the structurally complex model, "
+                        "plain vs surrogate-started")
+    p.add_argument("--plain-stride", type=int, default=64,
+                   help="complex2d: time the plain per-node build on every n-th node")
+    p.add_argument("--full-plain", action="store_true",
+                   help="complex2d: also build the plain per-node cache for every node and "
+                        "compare traveltimes at full size")
+    p.add_argument("--train-media", type=int, default=1000,
+                   help="complex2d: media in the surrogate's training cache (x 3 modes x 360)")
+    p.add_argument("--train-steps", type=int, default=4000)
+    p.add_argument("--cpu-nodes", type=int, default=40,
+                   help="complex2d: nodes in the CPU oracle's cache-build sample")
+    p.add_argument("--kmeans", type=int, nargs="*", default=[],
+                   help="complex2d: also trace k-means class caches with these K")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run 4 device-to-device copies of MIB MiB (HBM counter scale)")
     return p.parse_args()
@@ -96,6 +112,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "complex2d":
+        run_complex(args)
+        return
     if args.copy_calibration:
         # a plain copy of known size: FETCH_SIZE/WRITE_SIZE per dispatch of
         # this kernel against its true byte count gives the counter scale
@@ -269,6 +288,227 @@ def cpu_baseline(m, E, fields_per_step):
             "cores": 1, "kind": "oracle",
             "sample": "one full step of the same workload (cache build + Dijkstra for 3 modes)",
             "build_s": t1 - t0, "trace_s": t2 - t1, "cpu_count": os.cpu_count()}
+
+
+# --------------------------------------------------------------------------
+# Per-node caches of the structurally complex model (1701 x 351 at 10 m,
+# qSV, radius 5): plain vs surrogate-started cache build, traveltimes, and
+# optionally coarse k-means class caches against the per-node fields.
+
+def _events(torch, stream):
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    return a, b
+
+
+def _elapsed(torch, ev, stream):
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    return ev[0].elapsed_time(ev[1]) * 1e-3
+
+
+def _converged(status):
+    ok = (status & (1 | 4 | 8)) == 0  # not NO_BRACKET / FLUID / NONPHYS
+    return int(ok.sum())
+
+
+def _tau_rel(a, b):
+    fin = np.isfinite(b)
+    same = bool(np.array_equal(np.isfinite(a), fin))
+    rel = np.abs(a[fin] - b[fin]) / np.maximum(np.abs(b[fin]), 1e-300)
+    return {"max": float(rel.max()), "median": float(np.median(rel)),
+            "p99": float(np.quantile(rel, 0.99)), "same_reachability": same}
+
+
+def run_complex(args):
+    import torch
+    import paper_2609_26108_amd as C
+    import workloads as W
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    m = W.complex_2d()
+    rows = m.param_rows()
+    n = rows.shape[0]
+    params = torch.from_numpy(rows).to(dev)
+    classes = torch.empty((n, 13), dtype=torch.float64, device=dev)
+    C.chert_classes_from_thomsen(params, classes)
+    mode = m.modes[0]
+    sub = C.star_subset(m.radius, m.hx, m.hz)
+    desc = C.cache_desc(modes=(mode,), subset=sub)
+    out = {"metric": METRIC, "workload": "complex2d", "n_gpus": 1, "dtype": "f64",
+           "data": "synthetic (seeded workloads.complex_2d)",
+           "config": {"workload": f"structurally complex 2D, {m.nx}x{m.nz} @10 m, per-node "
+                                  "TTI+Q, qSV, radius 5, star-bin subset cache",
+                      "nodes": n, "columns": int(desc.n_cols), "sources": m.sources}}
+
+    # 1. surrogate: training cache of seeded media (full direction set, 3 modes)
+    t_rows = W.surrogate_training_rows(args.train_media)
+    Kt = t_rows.shape[0]
+    t_cls = torch.empty((Kt, 13), dtype=torch.float64, device=dev)
+    C.chert_classes_from_thomsen(torch.from_numpy(t_rows).to(dev), t_cls)
+    t_desc = C.cache_desc(modes=(0, 1, 2))
+    t_lay = C.chert_cache_layout_of(t_desc, Kt)
+    t_cache = torch.zeros(t_lay.total_bytes, dtype=torch.uint8, device=dev)
+    ev = _events(torch, stream)
+    C.chert_build_cache(t_desc, t_cls, Kt, t_cache, None, stream=stream)
+    t_build = _elapsed(torch, ev, stream)
+    ns = 3 * Kt * 360
+    x = torch.empty((ns, 16), dtype=torch.float32, device=dev)
+    y = torch.empty((ns, 4), dtype=torch.float32, device=dev)
+    ok = torch.empty(ns, dtype=torch.int32, device=dev)
+    C.chert_surrogate_dataset(t_desc, t_cache, t_cls, Kt, x, y, ok, stream=stream)
+    lay = C.chert_surrogate_layout_of()
+    blob = torch.zeros(lay.total_bytes, dtype=torch.uint8, device=dev)
+    C.chert_surrogate_init(blob, torch.from_numpy(W.mlp_init(C.SURROGATE_SHAPES, seed=1)).to(dev),
+                           stream=stream)
+    C.chert_surrogate_fit_norm(blob, x, y, ok, stream=stream)
+    C.chert_prof_enable(True, only="k_sg_grad")
+    ev = _events(torch, stream)
+    losses = C.train_surrogate(blob, x, y, ok, steps=args.train_steps, batch=2048, seed=2,
+                               stream=stream)
+    t_train = _elapsed(torch, ev, stream)
+    pg = C.chert_prof_read()["k_sg_grad"]
+    C.chert_prof_enable(False)
+    L = losses.cpu().numpy()
+    # forward 2*(16*128 + 2*128*128 + 128*4) FLOP per sample, backward twice that
+    flop_step = 3 * 2 * (16 * 128 + 2 * 128 * 128 + 128 * 4) * 2048
+    grad_us = 1e3 * pg[1] / max(pg[0], 1)
+    out["training"] = {
+        "media": Kt, "samples_usable": int(ok.sum().item()), "steps": args.train_steps,
+        "batch": 2048, "build_training_cache_s": t_build, "train_s": t_train,
+        "loss_first20": float(L[:20].mean()), "loss_last200": float(L[-200:].mean()),
+        "k_sg_grad_avg_us": grad_us,
+        "k_sg_grad_mfma_frac": flop_step / (grad_us * 1e-6) / 2.5e15}
+
+    # 2. surrogate-started per-node build of every node
+    lay_c = C.chert_cache_layout_of(desc, n)
+    warm = torch.zeros(lay_c.total_bytes, dtype=torch.uint8, device=dev)
+    wws = torch.empty(C.chert_build_cache_surrogate_workspace_bytes(desc, n), dtype=torch.uint8,
+                      device=dev)
+    wst = torch.zeros(C.WARM_NSTATS, dtype=torch.int64, device=dev)
+    C.chert_build_cache_surrogate(desc, classes, n, blob, warm, wws, wst, stream=stream)  # warm-up
+    torch.cuda.synchronize()
+    C.chert_prof_enable(True)
+    ev = _events(torch, stream)
+    C.chert_build_cache_surrogate(desc, classes, n, blob, warm, wws, wst, stream=stream)
+    t_warm = _elapsed(torch, ev, stream)
+    pw = C.chert_prof_read()
+    C.chert_prof_enable(False)
+    fw, sw = C.cache_views(warm, desc, n)
+    conv_warm = _converged(sw[mode].cpu().numpy())
+    wstats = dict(zip(C.WARM_STATS, wst.cpu().numpy().tolist()))
+    out["warm"] = {"build_s": t_warm, "converged_entries": conv_warm,
+                   "hamiltonian_solves_per_s": conv_warm / t_warm, "stats": wstats,
+                   "fallback_job_frac": wstats["fallback_jobs"] / max(wstats["jobs"], 1),
+                   "kernels_ms": {k: v[1] for k, v in pw.items()}}
+
+    # 3. plain per-node build on every plain_stride-th node (timing sample)
+    pick = np.arange(0, n, args.plain_stride)
+    cls_s = classes[torch.from_numpy(pick).to(dev)].contiguous()
+    ks = pick.size
+    lay_s = C.chert_cache_layout_of(desc, ks)
+    plain_s = torch.zeros(lay_s.total_bytes, dtype=torch.uint8, device=dev)
+    ev = _events(torch, stream)
+    C.chert_build_cache(desc, cls_s, ks, plain_s, None, stream=stream)
+    t_plain_s = _elapsed(torch, ev, stream)
+    fp_s, sp_s = C.cache_views(plain_s, desc, ks)
+    conv_s = _converged(sp_s[mode].cpu().numpy())
+    fwn = fw[:, mode].cpu().numpy()[:, pick]
+    fpn = fp_s[:, mode].cpu().numpy()
+    okm = (sp_s[mode].cpu().numpy() & (1 | 4 | 8)) == 0
+    same_status = bool(np.array_equal(sw[mode].cpu().numpy()[pick], sp_s[mode].cpu().numpy()))
+    relV = np.abs(fwn[0][okm] - fpn[0][okm]) / fpn[0][okm]
+    out["plain_sample"] = {"nodes": int(ks), "stride": args.plain_stride, "build_s": t_plain_s,
+                           "converged_entries": conv_s,
+                           "hamiltonian_solves_per_s": conv_s / t_plain_s,
+                           "warm_vs_plain_same_status": same_status,
+                           "warm_vs_plain_V_rel_max": float(relV.max()) if relV.size else 0.0}
+    out["surrogate_speedup_solves_per_s"] = (conv_warm / t_warm) / (conv_s / t_plain_s)
+
+    # 4. per-node traveltimes through the surrogate-started cache
+    grid = C.make_grid(m.nx, m.nz, m.hx, m.hz, m.radius, None)
+    stats = C.TraceStats()
+    opts = C.trace_opts(C.OUT_TAU_R | C.OUT_TAU_I | C.OUT_TSTAR | C.OUT_PRED_P, stats=stats)
+    S = len(m.sources)
+    tr = {k: torch.empty((S, n), dtype=torch.float64, device=dev) for k in ("r", "i", "t")}
+    pp = torch.empty((S, n), dtype=torch.int32, device=dev)
+    tws = torch.empty(C.chert_trace_workspace_bytes(desc, n, grid, S, opts), dtype=torch.uint8,
+                      device=dev)
+
+    def trace(cache):
+        ev = _events(torch, stream)
+        C.chert_trace_field(desc, cache, n, grid, mode, m.sources, opts, tr["r"], tr["i"],
+                            tr["t"], pp, None, tws, stream=stream)
+        return _elapsed(torch, ev, stream)
+    trace(warm)
+    t_trace = trace(warm)
+    tau_warm = tr["r"][0].cpu().numpy().copy()
+    ox, oz, _, _ = C.chert_star_2d(m.radius, m.hx, m.hz, 360)
+    E = useful_edges(m.nx, m.nz, ox, oz)
+    out["trace"] = {"fields": "tau_R, tau_I, pred_P, t*", "trace_s": t_trace,
+                    "useful_edges_per_field": E, "stats": stats.as_dict(),
+                    "edge_relaxations_per_s_tau_fields": 2 * E / t_trace}
+    if args.full_plain:
+        plain = torch.zeros(lay_c.total_bytes, dtype=torch.uint8, device=dev)
+        ev = _events(torch, stream)
+        C.chert_build_cache(desc, classes, n, plain, None, stream=stream)
+        t_plain = _elapsed(torch, ev, stream)
+        trace(plain)
+        out["plain_full"] = {"build_s": t_plain,
+                             "converged_entries": _converged(C.cache_views(plain, desc, n)[1][mode].cpu().numpy()),
+                             "tau_R_rel_warm_vs_plain": _tau_rel(tau_warm, tr["r"][0].cpu().numpy())}
+        out["plain_full"]["hamiltonian_solves_per_s"] = out["plain_full"]["converged_entries"] / t_plain
+        del plain
+
+    # 5. coarse k-means class caches against the per-node field
+    if args.kmeans:
+        out["kmeans"] = {}
+        for K in args.kmeans:
+            crow, cid = W.kmeans_classes(m, K, seed=W.seed_for(3))
+            kc = torch.empty((crow.shape[0], 13), dtype=torch.float64, device=dev)
+            C.chert_classes_from_thomsen(torch.from_numpy(crow).to(dev), kc)
+            kd = C.cache_desc(modes=(mode,))
+            klay = C.chert_cache_layout_of(kd, crow.shape[0])
+            kcache = torch.zeros(klay.total_bytes, dtype=torch.uint8, device=dev)
+            C.chert_build_cache(kd, kc, crow.shape[0], kcache, torch.empty(
+                max(C.chert_build_cache_workspace_bytes(kd, crow.shape[0]), 1), dtype=torch.uint8,
+                device=dev), stream=stream)
+            kg = C.make_grid(m.nx, m.nz, m.hx, m.hz, m.radius,
+                             torch.from_numpy(cid.reshape(-1).astype(np.int32)).to(dev))
+            ko = C.trace_opts(C.OUT_TAU_R)
+            kt = torch.empty((S, n), dtype=torch.float64, device=dev)
+            kws = torch.empty(C.chert_trace_workspace_bytes(kd, crow.shape[0], kg, S, ko),
+                              dtype=torch.uint8, device=dev)
+            ev = _events(torch, stream)
+            C.chert_trace_field(kd, kcache, crow.shape[0], kg, mode, m.sources, ko, kt, None,
+                                None, None, None, kws, stream=stream)
+            t_k = _elapsed(torch, ev, stream)
+            out["kmeans"][str(K)] = {"classes_incl_water": int(crow.shape[0]), "trace_s": t_k,
+                                     "tau_R_rel_vs_per_node": _tau_rel(kt[0].cpu().numpy(), tau_warm)}
+    if not args.no_cpu:
+        solid = pick[rows[pick, 1] > 0.0][:args.cpu_nodes]
+        out["cpu_baseline"] = cpu_baseline_complex(m, rows, sub, solid)
+    out["value"] = out["warm"]["hamiltonian_solves_per_s"]
+    out["unit"] = "converged per-node cache entries/s (surrogate-started build)"
+    out["higher_is_better"] = True
+    print(json.dumps(out))
+
+
+def cpu_baseline_complex(m, rows, sub, nodes):
+    """The CPU oracle as it stands: its plain cache build on a few nodes
+    (extrapolated per entry) and its Dijkstra on the full per-node field."""
+    import oracle as O
+    O.build(force=False)
+    cls = np.stack([O.class_from_thomsen(*r) for r in rows[nodes]])
+    t0 = time.perf_counter()
+    f, s = O.build_cache_2d(cls, mode_mask=1 << m.modes[0], subset=sub)
+    t1 = time.perf_counter()
+    conv = _converged(s[m.modes[0]])
+    return {"value": conv / (t1 - t0), "unit": "converged cache entries/s (plain oracle build)",
+            "cores": 1, "kind": "oracle",
+            "sample": f"plain cache build of {len(nodes)} solid nodes of the timing sample, "
+                      "qSV, star bins",
+            "build_s": t1 - t0, "cpu_count": os.cpu_count()}
 
 
 if __name__ == "__main__":

@@ -378,12 +378,14 @@ int chert_surrogate_adam(void *blob_dev, const float *grad_dev, int32_t step,
 int chert_surrogate_infer(const void *blob_dev, const float *x_dev, int64_t n,
                           float *y_dev, void *stream);
 
-/* Counters of a surrogate-started build (device int64[8]):
- * [0] (mode, class) jobs, [1] jobs sent to the plain solver, [2] directions
- * started from the surrogate, [3] of them near a fold of the ray-angle map,
- * [4] Newton not converged, [5] slope of the ray-angle map too small,
- * [6] theta_I not the root nearest 0, [7] residual or entry rejected. */
-enum { CHERT_WARM_NSTATS = 8 };
+/* Counters of a surrogate-started build (device int64[10]):
+ * [0] (mode, class) jobs, [1] jobs sent to the full plain solver,
+ * [2] directions, [3] of them near a fold of the ray-angle map (solved by
+ * the windowed plain search), [4] Newton not converged, [5] slope of the
+ * ray-angle map too small, [6] theta_I not the root nearest 0, [7] residual
+ * or entry rejected, [8] sweep samples evaluated by windowed searches,
+ * [9] jobs whose windowed search failed its guard. */
+enum { CHERT_WARM_NSTATS = 10 };
 
 /* Scratch needed by chert_build_cache_surrogate. */
 size_t chert_build_cache_surrogate_workspace_bytes(const chert_cache_desc *d,
@@ -399,10 +401,16 @@ size_t chert_build_cache_surrogate_workspace_bytes(const chert_cache_desc *d,
  *      within 2 degrees of the direction, the map's slope at the root is
  *      at least 0.05, theta_I is the root of the residual nearest 0, and
  *      the residual is at most resid_tol (0 = 1e-11);
- *   4. every (mode, class) job with a rejected direction is solved again by
- *      the plain path (sweep and brackets), so each entry equals the plain
- *      solver's to the Newton tolerance.
- * stats_dev: nullable device int64[CHERT_WARM_NSTATS], overwritten. */
+ *   4. directions near a fold are solved by the plain sweep-and-bracket
+ *      search restricted to the sweep samples whose theta_R the elastic map
+ *      sends within 2 degrees of the target (the rest of the sweep cannot
+ *      bracket it while the viscoelastic map stays within that margin of
+ *      the elastic one, which is checked on every evaluated sample);
+ *   5. every (mode, class) job with any other rejected direction, or a
+ *      failed check in 4, is solved again by the full plain path, so each
+ *      entry equals the plain solver's to the Newton tolerance.
+ * stats_dev: nullable device int64[CHERT_WARM_NSTATS], overwritten.
+ * UNSUPPORTED above 512 stored directions (n_dirs or n_subset). */
 int chert_build_cache_surrogate(const chert_cache_desc *d,
                                 const chert_class *classes_dev,
                                 int64_t n_classes, const void *blob_dev,

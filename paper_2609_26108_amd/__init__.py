@@ -40,9 +40,11 @@ EXPORTS = (
     "chert_surrogate_adam", "chert_surrogate_infer",
     "chert_build_cache_surrogate_workspace_bytes", "chert_build_cache_surrogate",
 )
-WARM_NSTATS = 8
+WARM_NSTATS = 10
+# parameter blocks of the surrogate, in their order in the parameter vector
+SURROGATE_SHAPES = [(16, 128), (128,), (128, 128), (128,), (128, 128), (128,), (128, 4), (4,)]
 WARM_STATS = ("jobs", "fallback_jobs", "directions", "fold", "newton_fail", "slope",
-              "theta_i_not_nearest", "rejected")
+              "theta_i_not_nearest", "rejected", "window_samples", "window_guard_failed")
 
 
 class ChertError(RuntimeError):

@@ -526,11 +526,43 @@ __device__ __forceinline__ int fold_bin(double psi) {
 }
 
 // one wavefront per (mode, class) job
+// sweep samples whose theta_R the elastic map sends within kFoldMargin of
+// psi_star (either half of the circle), plus one sample on each side
+__device__ __forceinline__ void mark_window(const SolveArgs& a, const double* psi, double psi_star,
+                                            uint32_t* mask) {
+  const double dth = kTwoPi / a.n_sweep;
+  for (int j = threadIdx.x; j < kProxyN; j += blockDim.x) {
+    const double pa = psi[j];
+    const double pb = j + 1 < kProxyN ? psi[j + 1] : psi[0] + kPi;
+    const double dp = wrap_pi(pb - pa);
+    const double lo = fmin(pa, pa + dp) - kFoldMargin;
+    const double width = fabs(dp) + 2.0 * kFoldMargin;
+    for (int half = 0; half < 2; ++half) {
+      double off = fmod(psi_star - half * kPi - lo, kTwoPi);
+      if (off < 0.0) off += kTwoPi;
+      if (off > width) continue;
+      const double ta = (j + 0.5) * (kPi / kProxyN) + half * kPi;
+      const double tb = ta + kPi / kProxyN;
+      const int i0 = (int)floor(ta / dth - 0.5) - 1;
+      const int i1 = (int)ceil(tb / dth - 0.5) + 1;
+      for (int i = i0; i <= i1; ++i) {
+        const int q = ((i % a.n_sweep) + a.n_sweep) % a.n_sweep;
+        atomicOr(&mask[q >> 5], 1u << (q & 31));
+      }
+    }
+  }
+}
+
 __global__ void __launch_bounds__(64) k_warm_solve(WarmArgs w) {
+  extern __shared__ double2 tab[];  // windowed sweep table [n_sweep], then the sample list
   __shared__ double s_psi[kProxyN];
   __shared__ uint32_t s_fold[kFoldWords];
   __shared__ uint32_t s_cnt[CHERT_WARM_NSTATS];
-  __shared__ int s_all;
+  __shared__ uint32_t s_mask[kMaxSweep / 32];
+  __shared__ int16_t s_flag[kMaxSubset / 2];
+  __shared__ int s_br[64 * kMaxBr];
+  __shared__ int s_all, s_nflag, s_nlist, s_bad;
+
   const SolveArgs& a = w.so;
   const int64_t job = blockIdx.x;
   const int lane = threadIdx.x;
@@ -538,9 +570,14 @@ __global__ void __launch_bounds__(64) k_warm_solve(WarmArgs w) {
   const int mode = a.modes[job / a.n_classes];
   const chert_class c = a.classes[k];
   const int64_t row = ((int64_t)mode * a.n_classes + k) * a.n_cols;
+  int16_t* s_list = reinterpret_cast<int16_t*>(tab + a.n_sweep);
   if (lane < CHERT_WARM_NSTATS) s_cnt[lane] = 0;
   if (lane < kFoldWords) s_fold[lane] = 0;
-  if (lane == 0) s_all = 0;
+  if (lane == 0) {
+    s_all = 0;
+    s_nflag = 0;
+    s_bad = 0;
+  }
   const int32_t blocked = class_block(c, mode);
   if (blocked) {
     Entry none{};
@@ -594,9 +631,13 @@ __global__ void __launch_bounds__(64) k_warm_solve(WarmArgs w) {
     const double psi_star = dir_psi(a, d, m.tilt);
     atomicAdd(&s_cnt[2], 1u);
     const int fb = fold_bin(psi_star);
-    if (s_all || (s_fold[fb >> 5] >> (fb & 31)) & 1u) {
-      atomicAdd(&s_cnt[3], 1u);
+    if (s_all) {
       reject = true;
+      continue;
+    }
+    if ((s_fold[fb >> 5] >> (fb & 31)) & 1u) {  // near a fold: windowed plain search below
+      atomicAdd(&s_cnt[3], 1u);
+      s_flag[atomicAdd(&s_nflag, 1)] = (int16_t)sidx;
       continue;
     }
     const float2 p = w.pred[job * a.n_solve + sidx];
@@ -633,8 +674,68 @@ __global__ void __launch_bounds__(64) k_warm_solve(WarmArgs w) {
     }
     store_pair(a, row, col, pcol, e, m.tilt, CHERT_ST_OK);
   }
-  const bool any = __any(reject);
+  bool any = __any(reject);
   __syncthreads();
+
+  // Directions near a fold: the plain sweep-and-bracket search, evaluated
+  // only at the sweep samples the elastic map places within kFoldMargin of
+  // the target ray angle.  Samples left out stay NaN and so never bracket;
+  // the search is the plain one wherever the viscoelastic map stays within
+  // kFoldMargin of the elastic one, which is checked on every evaluated
+  // sample (half the margin; otherwise the job goes to the plain path).
+  const int nflag = s_nflag;
+  if (!any && nflag > 0) {
+    for (int i = lane; i < a.n_sweep; i += 64) tab[i] = make_double2(0.0, NAN);
+    for (int i = lane; i < (a.n_sweep + 31) / 32; i += 64) s_mask[i] = 0u;
+    __syncthreads();
+    for (int f = 0; f < nflag; ++f) {
+      int d, col, pcol;
+      dir_cols(a, s_flag[f], &d, &col, &pcol);
+      mark_window(a, s_psi, dir_psi(a, d, m.tilt), s_mask);
+    }
+    __syncthreads();
+    if (lane == 0) {
+      int nl = 0;
+      for (int wd = 0; wd < (a.n_sweep + 31) / 32; ++wd) {
+        uint32_t bits = s_mask[wd];
+        while (bits) {
+          const int b = __builtin_ctz(bits);
+          bits &= bits - 1u;
+          s_list[nl++] = (int16_t)(wd * 32 + b);
+        }
+      }
+      s_nlist = nl;
+    }
+    __syncthreads();
+    const int nl = s_nlist;
+    for (int q = lane; q < nl; q += 64) {
+      const int i = s_list[q];
+      const double thR = (i + 0.5) * (kTwoPi / a.n_sweep);
+      double thI;
+      double2 out = make_double2(0.0, NAN);
+      if (theta_imag(m, mode, a.kernel, thR, &thI)) {
+        const double psi = ray_angle(energy_velocity(m, mode, a.kernel, thR, thI));
+        if (isfinite(psi)) out = make_double2(thI, psi);
+        const double pe = ray_angle(energy_velocity(me, mode, a.kernel, thR, 0.0));
+        if (!(fabs(wrap_pi(psi - pe)) <= 0.5 * kFoldMargin)) s_bad = 1;
+      }
+      tab[i] = out;
+    }
+    if (lane == 0) atomicAdd(&s_cnt[8], (uint32_t)nl);
+    __syncthreads();
+    if (s_bad) {
+      any = true;
+      if (lane == 0) s_cnt[9] = 1;
+    } else {
+      for (int f = lane; f < nflag; f += 64) {
+        int d, col, pcol;
+        dir_cols(a, s_flag[f], &d, &col, &pcol);
+        Entry best{};
+        const int32_t st = solve_dir(a, m, mode, tab, d, s_br + lane * kMaxBr, &best);
+        store_pair(a, row, col, pcol, best, m.tilt, st);
+      }
+    }
+  }
   if (lane == 0) {
     s_cnt[0] = 1;
     if (any) {
@@ -819,6 +920,8 @@ extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
   uint8_t* cache = (uint8_t*)cache_dev;
   WarmArgs w{};
   w.so = solve_args(d, classes_dev, n_classes, cache, lay, nullptr);
+  if (w.so.n_solve > kMaxSubset / 2)
+    return fail(CHERT_ERR_UNSUPPORTED, "surrogate-started builds take at most 512 directions");
   const int64_t jobs = (int64_t)w.so.n_modes * n_classes;
   const int64_t rows = jobs * w.so.n_solve;
   uint8_t* ws = (uint8_t*)workspace_dev;
@@ -837,7 +940,8 @@ extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
     if (blocks > 0x7fffffffLL) return fail(CHERT_ERR_INVALID_ARG, "too many entries");
     CHERT_LAUNCH("k_warm_predict", k_warm_predict, dim3((unsigned)blocks), dim3(mlp::kThreads),
                  0, s, w, rows);
-    CHERT_LAUNCH("k_warm_solve", k_warm_solve, dim3((unsigned)jobs), dim3(64), 0, s, w);
+    CHERT_LAUNCH("k_warm_solve", k_warm_solve, dim3((unsigned)jobs), dim3(64),
+                 (size_t)d->n_sweep * (sizeof(double2) + sizeof(int16_t)), s, w);
     const int64_t grid = jobs < 4096 ? jobs : 4096;
     CHERT_LAUNCH("k_build_fused", k_build_fused, dim3((unsigned)grid), dim3(kNodeThreads),
                  (size_t)d->n_sweep * sizeof(double2), s, w.so, (const int32_t*)w.fb_list,

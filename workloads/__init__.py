@@ -267,3 +267,28 @@ def mlp_init(shapes, seed=0):
         else:
             parts.append(np.zeros(shp).reshape(-1))
     return np.concatenate(parts).astype(np.float32)
+
+
+def kmeans_classes(model, K, seed=0, max_iter=100):
+    """Group a per-node model into K property classes, as a user of the
+    class-cache method would: k-means (k-means++ seeding, Lloyd iterations)
+    on the standardised (Vp0, eps, delta, gamma, tilt, log Qp) of the solid
+    nodes; each class takes the mean parameters of its members.  Fluid
+    nodes (Vs0 = 0) form one extra class, last.  Returns (rows [K(+1), 10]
+    in param_rows order, class_id [nz, nx] int32)."""
+    rows = model.param_rows()
+    solid = rows[:, 1] > 0.0
+    feats = np.stack([rows[:, 0], rows[:, 3], rows[:, 4], rows[:, 5], rows[:, 6],
+                      np.log(rows[:, 8])], axis=1)[solid]
+    mu, sd = feats.mean(0), feats.std(0)
+    z = (feats - mu) / np.where(sd > 0, sd, 1.0)
+    from sklearn.cluster import KMeans
+    km = KMeans(n_clusters=K, init="k-means++", n_init=1, max_iter=max_iter,
+                random_state=seed, algorithm="lloyd").fit(z)
+    lab = km.labels_.astype(np.int32)
+    crow = np.stack([rows[solid][lab == k].mean(0) for k in range(K)])
+    cid = np.full(rows.shape[0], K, np.int32)
+    cid[solid] = lab
+    if (~solid).any():
+        crow = np.concatenate([crow, rows[~solid].mean(0, keepdims=True)])
+    return crow, cid.reshape(model.nz, model.nx)
