@@ -77,10 +77,11 @@ def parse():
     p.add_argument("--tile", type=int, nargs=2, default=(0, 0), metavar=("TX", "TZ"),
                    help="relaxation tile shape (0 0 = library default)")
     p.add_argument("--push-group", type=int, default=0, help="offsets per push item (1, 2, 4)")
-    p.add_argument("--workload", choices=("layered", "complex2d"), default="layered",
+    p.add_argument("--workload", choices=("layered", "complex2d", "shots"), default="layered",
                    help="layered: the 5-layer model (default, the headline line); "
                         "complex2d: per-node caches of the structurally complex model, "
-                        "plain vs surrogate-started")
+                        "plain vs surrogate-started; shots: 128 shots over 4 uneven "
+                        "per-node grids in one batch (autotuned, eager and graph)")
     p.add_argument("--plain-stride", type=int, default=64,
                    help="complex2d: time the plain per-node build on every n-th node")
     p.add_argument("--full-plain", action="store_true",
@@ -114,6 +115,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "complex2d":
         run_complex(args)
+        return
+    if args.workload == "shots":
+        run_shots(args)
         return
     if args.copy_calibration:
         # a plain copy of known size: FETCH_SIZE/WRITE_SIZE per dispatch of
@@ -320,28 +324,12 @@ def _tau_rel(a, b):
             "p99": float(np.quantile(rel, 0.99)), "same_reachability": same}
 
 
-def run_complex(args):
+def train_surrogate(args, dev, stream):
+    """Train the cache-solve surrogate on plain-solver entries of seeded
+    media (full direction set, 3 modes); returns (blob, info)."""
     import torch
     import paper_2609_26108_amd as C
     import workloads as W
-    dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream()
-    m = W.complex_2d()
-    rows = m.param_rows()
-    n = rows.shape[0]
-    params = torch.from_numpy(rows).to(dev)
-    classes = torch.empty((n, 13), dtype=torch.float64, device=dev)
-    C.chert_classes_from_thomsen(params, classes)
-    mode = m.modes[0]
-    sub = C.star_subset(m.radius, m.hx, m.hz)
-    desc = C.cache_desc(modes=(mode,), subset=sub)
-    out = {"metric": METRIC, "workload": "complex2d", "n_gpus": 1, "dtype": "f64",
-           "data": "synthetic (seeded workloads.complex_2d)",
-           "config": {"workload": f"structurally complex 2D, {m.nx}x{m.nz} @10 m, per-node "
-                                  "TTI+Q, qSV, radius 5, star-bin subset cache",
-                      "nodes": n, "columns": int(desc.n_cols), "sources": m.sources}}
-
-    # 1. surrogate: training cache of seeded media (full direction set, 3 modes)
     t_rows = W.surrogate_training_rows(args.train_media)
     Kt = t_rows.shape[0]
     t_cls = torch.empty((Kt, 13), dtype=torch.float64, device=dev)
@@ -373,12 +361,38 @@ def run_complex(args):
     # forward 2*(16*128 + 2*128*128 + 128*4) FLOP per sample, backward twice that
     flop_step = 3 * 2 * (16 * 128 + 2 * 128 * 128 + 128 * 4) * 2048
     grad_us = 1e3 * pg[1] / max(pg[0], 1)
-    out["training"] = {
+    info = {
         "media": Kt, "samples_usable": int(ok.sum().item()), "steps": args.train_steps,
         "batch": 2048, "build_training_cache_s": t_build, "train_s": t_train,
         "loss_first20": float(L[:20].mean()), "loss_last200": float(L[-200:].mean()),
         "k_sg_grad_avg_us": grad_us,
         "k_sg_grad_mfma_frac": flop_step / (grad_us * 1e-6) / 2.5e15}
+
+    return blob, info
+
+
+def run_complex(args):
+    import torch
+    import paper_2609_26108_amd as C
+    import workloads as W
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    m = W.complex_2d()
+    rows = m.param_rows()
+    n = rows.shape[0]
+    params = torch.from_numpy(rows).to(dev)
+    classes = torch.empty((n, 13), dtype=torch.float64, device=dev)
+    C.chert_classes_from_thomsen(params, classes)
+    mode = m.modes[0]
+    sub = C.star_subset(m.radius, m.hx, m.hz)
+    desc = C.cache_desc(modes=(mode,), subset=sub)
+    out = {"metric": METRIC, "workload": "complex2d", "n_gpus": 1, "dtype": "f64",
+           "data": "synthetic (seeded workloads.complex_2d)",
+           "config": {"workload": f"structurally complex 2D, {m.nx}x{m.nz} @10 m, per-node "
+                                  "TTI+Q, qSV, radius 5, star-bin subset cache",
+                      "nodes": n, "columns": int(desc.n_cols), "sources": m.sources}}
+
+    blob, out["training"] = train_surrogate(args, dev, stream)
 
     # 2. surrogate-started per-node build of every node
     lay_c = C.chert_cache_layout_of(desc, n)
@@ -492,6 +506,134 @@ def run_complex(args):
     out["unit"] = "converged per-node cache entries/s (surrogate-started build)"
     out["higher_is_better"] = True
     print(json.dumps(out))
+
+
+SHOT_GRIDS = ((401, 201), (801, 401), (1201, 301), (1701, 351))
+
+
+def shot_models():
+    """Four grids of uneven size from the structurally complex generator at
+    10 m (200 m of water kept; layers and faults scaled to the extent), 32
+    seafloor sources each at ix = round((j + 1/2) nx / 32)."""
+    import workloads as W
+    out = []
+    for g, (nx, nz) in enumerate(SHOT_GRIDS):
+        depth = (nz - 1) * 10.0
+        m = W.complex_2d(nx=nx, nz=nz, h=10.0, seed=W.seed_for(4) * 10 + g,
+                         n_layers=max(5, min(30, round(30 * depth / 3500.0))),
+                         n_faults=max(1, round(5 * nx / 1701)), modes=(0, 1), radius=5)
+        iz = 20  # first row below the water
+        m.sources = [int(round((j + 0.5) * nx / 32)) + nx * iz for j in range(32)]
+        out.append(m)
+    return out
+
+
+def run_shots(args):
+    import torch
+    import paper_2609_26108_amd as C
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    models = shot_models()
+    blob, tinfo = train_surrogate(args, dev, stream)
+    res = {"metric": METRIC, "workload": "shots", "n_gpus": 1, "dtype": "f64",
+           "data": "synthetic (seeded workloads.complex_2d, four extents)",
+           "config": {"workload": "128 shots over 4 uneven per-node grids (401x201, 801x401, "
+                                  "1201x301, 1701x351 @10 m), qP+qSV, radius 5, tau_R + pred + t*",
+                      "grids": [[m.nx, m.nz] for m in models], "sources_per_grid": 32,
+                      "modes": [0, 1]},
+           "training": tinfo}
+    b = C.Batch()
+    keep, caches = [], []
+    build = {"plain_s": 0.0, "warm_s": 0.0, "entries": 0}
+    E_total = 0
+    ox, oz, _, _ = C.chert_star_2d(5, 10.0, 10.0, 360)
+    for m in models:
+        rows = m.param_rows()
+        n = rows.shape[0]
+        cls = torch.empty((n, 13), dtype=torch.float64, device=dev)
+        C.chert_classes_from_thomsen(torch.from_numpy(rows).to(dev), cls)
+        desc = C.cache_desc(modes=(0, 1), subset=C.star_subset(5, m.hx, m.hz))
+        lay = C.chert_cache_layout_of(desc, n)
+        plain = torch.zeros(lay.total_bytes, dtype=torch.uint8, device=dev)
+        ev = _events(torch, stream)
+        C.chert_build_cache(desc, cls, n, plain, None, stream=stream)
+        build["plain_s"] += _elapsed(torch, ev, stream)
+        warm = torch.zeros(lay.total_bytes, dtype=torch.uint8, device=dev)
+        wws = torch.empty(C.chert_build_cache_surrogate_workspace_bytes(desc, n),
+                          dtype=torch.uint8, device=dev)
+        ev = _events(torch, stream)
+        C.chert_build_cache_surrogate(desc, cls, n, blob, warm, wws, None, stream=stream)
+        build["warm_s"] += _elapsed(torch, ev, stream)
+        del wws
+        build["entries"] += _converged(C.cache_views(warm, desc, n)[1][:2].cpu().numpy())
+        grid = C.make_grid(m.nx, m.nz, m.hx, m.hz, m.radius, None)
+        for mode in (0, 1):
+            S = len(m.sources)
+            out = dict(tau_r=torch.empty((S, n), dtype=torch.float64, device=dev),
+                       tstar=torch.empty((S, n), dtype=torch.float64, device=dev),
+                       pred_p=torch.empty((S, n), dtype=torch.int32, device=dev))
+            b.add(desc, warm, n, grid, mode, m.sources, **out)
+            keep.append((m, mode, out))
+        caches.append((m, desc, cls, plain, warm, grid))
+        E_total += useful_edges(m.nx, m.nz, ox, oz) * 2 * len(m.sources)
+    res["cache_build"] = {**build, "surrogate_gain": build["plain_s"] / build["warm_s"],
+                          "hamiltonian_solves_per_s_plain": build["entries"] / build["plain_s"],
+                          "hamiltonian_solves_per_s_warm": build["entries"] / build["warm_s"]}
+    outs = C.OUT_TAU_R | C.OUT_PRED_P | C.OUT_TSTAR
+    opts = C.trace_opts(outs)
+    ws = torch.empty(C.chert_trace_autotune_workspace_bytes(b, opts), dtype=torch.uint8,
+                     device=dev)
+    t0 = time.perf_counter()
+    probe_ms = C.chert_trace_autotune(b, opts, ws, stream=stream)
+    res["autotune"] = {"s": time.perf_counter() - t0, "probe_ms": probe_ms,
+                       "tile": [opts.tile_x, opts.tile_z], "push_group": opts.push_group,
+                       "launch": ["per_round", "persistent"][opts.launch]}
+    stats = C.TraceStats()
+    opts_s = C.trace_opts(outs, opts.tile_x, opts.tile_z, push_group=opts.push_group,
+                          launch=opts.launch, stats=stats)
+    ev = _events(torch, stream)
+    C.chert_trace_batch(b, opts_s, ws, stream=stream)
+    t_eager = _elapsed(torch, ev, stream)
+    shots = 2 * sum(len(m.sources) for m in models)
+    res["eager"] = {"s": t_eager, "shots_per_s": shots / t_eager,
+                    "star_edges_per_s_tau_fields": E_total / t_eager, "stats": stats.as_dict()}
+    # one persistent graph of the whole batch, replayed
+    gopts = C.trace_opts(outs, opts.tile_x, opts.tile_z, push_group=opts.push_group,
+                         launch=C.LAUNCH_PERSISTENT)
+    gs = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(gs):
+        graph = C.TraceGraph(b, gopts, ws, stream=gs)
+        graph.launch(gs)
+        graph.finish(None, gs)
+        ev = _events(torch, gs)
+        graph.launch(gs)
+        t_graph = _elapsed(torch, ev, gs)
+        st = C.TraceStats()
+        graph.finish(st, gs)
+    graph.close()
+    res["graph"] = {"s": t_graph, "shots_per_s": shots / t_graph, "rounds": list(st.rounds)}
+    # surrogate form vs plain form: one shot per grid and mode traced on the
+    # plain cache with chert_trace_field, against the batch (warm cache)
+    worst = 0.0
+    for (m, desc, cls, plain, warm, grid) in caches:
+        n = m.n_nodes
+        o1 = C.trace_opts(C.OUT_TAU_R)
+        t1 = torch.empty((1, n), dtype=torch.float64, device=dev)
+        w1 = torch.empty(C.chert_trace_workspace_bytes(desc, n, grid, 1, o1), dtype=torch.uint8,
+                         device=dev)
+        for mode in (0, 1):
+            C.chert_trace_field(desc, plain, n, grid, mode, m.sources[:1], o1, t1, None, None,
+                                None, None, w1, stream=stream)
+            bt = [o for (mm, md, o) in keep if mm is m and md == mode][0]["tau_r"][0]
+            r = _tau_rel(bt.cpu().numpy(), t1[0].cpu().numpy())
+            worst = max(worst, r["max"])
+        del w1
+    res["tau_R_rel_surrogate_vs_plain_max"] = worst
+    res["value"] = res["graph"]["shots_per_s"]
+    res["unit"] = "shots/s ((source, mode) fields with tau_R + pred + t*, one graph replay)"
+    res["higher_is_better"] = True
+    print(json.dumps(res))
 
 
 def cpu_baseline_complex(m, rows, sub, nodes):

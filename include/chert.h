@@ -211,6 +211,18 @@ typedef struct chert_trace_stats {
   int32_t reserved2;
 } chert_trace_stats;
 
+/* How the relaxation rounds are launched (the fields are the same either
+ * way: the fixed point does not depend on the schedule):
+ *   PER_ROUND   one launch per round over every tile; the host checks for
+ *               termination every 8 rounds;
+ *   PERSISTENT  one launch per phase: an occupancy-sized grid walks each
+ *               round's active tiles, rounds separated by a device-wide
+ *               barrier (bounded wait: a stalled barrier fails the call with
+ *               CHERT_ERR_HIP instead of hanging); the host waits only at
+ *               the end, and the launch sequence can be captured into a
+ *               graph (chert_trace_graph_create). */
+enum { CHERT_LAUNCH_PER_ROUND = 0, CHERT_LAUNCH_PERSISTENT = 1 };
+
 typedef struct chert_trace_opts {
   uint32_t outputs;   /* CHERT_OUT_* bits.  TSTAR needs TAU_R and PRED_P;
                          PRED_P needs TAU_R; PRED_A needs TAU_I.           */
@@ -218,7 +230,7 @@ typedef struct chert_trace_opts {
   int32_t tile_z;     /* relaxation tile height in nodes (0 = default 32)  */
   int32_t max_rounds; /* cap on relaxation rounds per phase (0 = default)  */
   int32_t push_group; /* star offsets per push work item: 1, 2 or 4 (0 = 2) */
-  int32_t reserved;   /* must be 0                                          */
+  int32_t launch;     /* CHERT_LAUNCH_PER_ROUND (0) or _PERSISTENT (1)      */
   chert_trace_stats *stats_host; /* nullable: filled when the call returns */
 } chert_trace_opts;
 
@@ -273,6 +285,44 @@ size_t chert_trace_batch_workspace_bytes(const chert_trace_job *jobs, int32_t n_
 int chert_trace_batch(const chert_trace_job *jobs, int32_t n_jobs,
                       const chert_trace_opts *o, void *workspace_dev,
                       size_t workspace_bytes, void *stream);
+
+/* Autotuner of the relaxation's launch parameters for a given batch.  The
+ * fixed point does not depend on them (every candidate gives the same
+ * fields); only the time does.  Candidates: tile shapes 32x32, 64x16,
+ * 16x64, 32x16, 16x32, 128x8; push groups 1, 2, 4; per-round and persistent
+ * launch.  Each is timed (HIP events, second of two runs) on a probe batch
+ * made of the first source of every job; the fastest is written into
+ * o->tile_x, tile_z, push_group and launch (other fields are kept) and its
+ * probe time into *best_ms (nullable).  The probe writes the first source's
+ * rows of the jobs' outputs.  The workspace must hold
+ * chert_trace_autotune_workspace_bytes (which also covers the full batch
+ * under any candidate).  Synchronous. */
+size_t chert_trace_autotune_workspace_bytes(const chert_trace_job *jobs, int32_t n_jobs,
+                                            const chert_trace_opts *o);
+int chert_trace_autotune(const chert_trace_job *jobs, int32_t n_jobs,
+                         chert_trace_opts *o, void *workspace_dev,
+                         size_t workspace_bytes, void *stream, double *best_ms);
+
+/* The whole of a chert_trace_batch call as one replayable HIP graph
+ * (persistent launch only): create plans the batch, uploads its tables into
+ * workspace_dev (synchronously on `stream`, which must not be NULL) and
+ * captures every kernel -- edge weights, field initialisation, the three
+ * persistent relaxation phases, predecessors and t* -- from stream capture
+ * of `stream`.  launch enqueues one replay (asynchronous, no host work);
+ * finish waits on `stream` and reports that replay's errors and counters
+ * like chert_trace_batch; destroy releases the graph.  Outputs, caches and
+ * the workspace named at create time must stay allocated while the graph
+ * exists; their contents may change between replays (e.g. a rebuilt cache).
+ * One replay at a time per workspace. */
+typedef struct chert_trace_graph chert_trace_graph;
+int chert_trace_graph_create(const chert_trace_job *jobs, int32_t n_jobs,
+                             const chert_trace_opts *o, void *workspace_dev,
+                             size_t workspace_bytes, void *stream,
+                             chert_trace_graph **out);
+int chert_trace_graph_launch(chert_trace_graph *g, void *stream);
+int chert_trace_graph_finish(chert_trace_graph *g, void *stream,
+                             chert_trace_stats *stats_host);
+int chert_trace_graph_destroy(chert_trace_graph *g);
 
 /* Raypath (eqs 25, 33-34): follow pred from rcv back to src and write the
  * node sequence src ... rcv into path_out.  Host, synchronous.

@@ -27,6 +27,7 @@ FIELDS = ("V", "A", "Q", "rx", "rz", "thR", "thI", "res")
 NF = len(FIELDS)
 OUT_TAU_R, OUT_TAU_I, OUT_TSTAR, OUT_PRED_P, OUT_PRED_A = 1, 2, 4, 8, 16
 OUT_ALL = 31
+LAUNCH_PER_ROUND, LAUNCH_PERSISTENT = 0, 1
 
 EXPORTS = (
     "chert_class_from_thomsen", "chert_classes_from_thomsen", "chert_cache_layout_of",
@@ -39,6 +40,8 @@ EXPORTS = (
     "chert_surrogate_fit_norm", "chert_surrogate_grad_workspace_bytes", "chert_surrogate_grad",
     "chert_surrogate_adam", "chert_surrogate_infer",
     "chert_build_cache_surrogate_workspace_bytes", "chert_build_cache_surrogate",
+    "chert_trace_graph_create", "chert_trace_graph_launch", "chert_trace_graph_finish",
+    "chert_trace_graph_destroy", "chert_trace_autotune_workspace_bytes", "chert_trace_autotune",
 )
 WARM_NSTATS = 10
 # parameter blocks of the surrogate, in their order in the parameter vector
@@ -110,7 +113,7 @@ class TraceStats(ctypes.Structure):
 class TraceOpts(ctypes.Structure):
     _fields_ = [("outputs", ctypes.c_uint32), ("tile_x", ctypes.c_int32),
                 ("tile_z", ctypes.c_int32), ("max_rounds", ctypes.c_int32),
-                ("push_group", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("push_group", ctypes.c_int32), ("launch", ctypes.c_int32),
                 ("stats_host", ctypes.c_void_p)]
 
 
@@ -173,6 +176,13 @@ def lib():
         L.chert_build_cache_surrogate_workspace_bytes.argtypes = [P, i64]
         L.chert_build_cache_surrogate_workspace_bytes.restype = sz
         L.chert_build_cache_surrogate.argtypes = [P, P, i64, P, d, P, P, P, sz, P]
+        L.chert_trace_graph_create.argtypes = [P, i32, P, P, sz, P, P]
+        L.chert_trace_graph_launch.argtypes = [P, P]
+        L.chert_trace_graph_finish.argtypes = [P, P, P]
+        L.chert_trace_graph_destroy.argtypes = [P]
+        L.chert_trace_autotune_workspace_bytes.argtypes = [P, i32, P]
+        L.chert_trace_autotune_workspace_bytes.restype = sz
+        L.chert_trace_autotune.argtypes = [P, i32, P, P, sz, P, P]
         _lib = L
     return _lib
 
@@ -300,9 +310,11 @@ def make_grid(nx, nz, hx, hz, radius, class_id_dev):
     return g
 
 
-def trace_opts(outputs=OUT_ALL, tile_x=0, tile_z=0, max_rounds=0, stats=None, push_group=0):
-    """stats: a TraceStats to fill (kept referenced by the returned options)."""
-    o = TraceOpts(outputs, tile_x, tile_z, max_rounds, push_group, 0,
+def trace_opts(outputs=OUT_ALL, tile_x=0, tile_z=0, max_rounds=0, stats=None, push_group=0,
+               launch=0):
+    """stats: a TraceStats to fill (kept referenced by the returned options);
+    launch: LAUNCH_PER_ROUND or LAUNCH_PERSISTENT."""
+    o = TraceOpts(outputs, tile_x, tile_z, max_rounds, push_group, launch,
                   ctypes.addressof(stats) if stats is not None else None)
     o._stats = stats
     return o
@@ -489,6 +501,59 @@ def surrogate_views(blob_dev):
 
 
 # ------------------------------------------------------------ cache views --
+
+def chert_trace_autotune_workspace_bytes(batch, opts):
+    arr, n = batch.array()
+    return int(lib().chert_trace_autotune_workspace_bytes(arr, n, ctypes.byref(opts)))
+
+
+def chert_trace_autotune(batch, opts, workspace_dev, stream=None):
+    """Updates opts in place (tile, push group, launch); returns the probe's
+    time in ms."""
+    arr, n = batch.array()
+    ms = ctypes.c_double(0.0)
+    _check(lib().chert_trace_autotune(arr, n, ctypes.byref(opts), _ptr(workspace_dev),
+                                      _nbytes(workspace_dev), _stream(stream), ctypes.byref(ms)))
+    return ms.value
+
+
+class TraceGraph:
+    """A chert_trace_batch captured as one HIP graph (persistent launch).
+    Keeps the batch, options and workspace referenced while it lives."""
+
+    def __init__(self, batch, opts, workspace_dev, stream=None):
+        import torch
+        self._keep = (batch, opts, workspace_dev)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        arr, n = batch.array()
+        h = ctypes.c_void_p()
+        _check(lib().chert_trace_graph_create(arr, n, ctypes.byref(opts),
+                                              _ptr(workspace_dev), _nbytes(workspace_dev),
+                                              _stream(stream), ctypes.byref(h)))
+        self._arr = arr
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(lib().chert_trace_graph_launch(self.handle, _stream(stream or self._stream)))
+
+    def finish(self, stats=None, stream=None):
+        _check(lib().chert_trace_graph_finish(
+            self.handle, _stream(stream or self._stream),
+            ctypes.byref(stats) if stats is not None else None))
+
+    def close(self):
+        if self.handle:
+            lib().chert_trace_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
 
 def cache_views(cache_dev, desc, n_classes):
     """(fields [NF][3][K][n_dirs] float64, status [3][K][n_dirs] int32) views

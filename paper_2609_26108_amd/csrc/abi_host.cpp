@@ -95,6 +95,14 @@ void prof_end(int slot, hipStream_t s) {
   hipEventRecord(g_prof[slot].stop, s);
 }
 
+bool prof_suspend() {
+  const bool was = g_prof_on;
+  g_prof_on = false;
+  return was;
+}
+
+void prof_resume(bool was) { g_prof_on = was; }
+
 static void prof_recycle() {
   for (auto& r : g_prof) {
     g_pool.push_back(r.start);

@@ -29,6 +29,10 @@ int star_2d(int R, double hx, double hz, int n_dirs, int32_t* ox, int32_t* oz, d
 // off) after recording a start event on the stream; prof_end records the stop.
 int prof_begin(const char* name, hipStream_t s);
 void prof_end(int slot, hipStream_t s);
+// Turn event bracketing off (returns the previous state) and back on, around
+// work that is captured into a graph.
+bool prof_suspend();
+void prof_resume(bool was);
 
 }  // namespace chert
 

@@ -25,6 +25,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <new>
 #include <vector>
 
 #include "chert.h"
@@ -97,7 +98,8 @@ struct RelaxArgs {
   const int32_t* ox;
   const int32_t* oz;
   int32_t* flags;    // [2][n_tiles]
-  int32_t* counter;  // [max_rounds + 2]
+  int32_t* list;     // [2][n_tiles] tiles active in a round (by round parity)
+  int32_t* counter;  // [max_rounds + 2] tiles active in each round
   int32_t* err;      // out-of-range class ids seen
   unsigned long long* stats;  // [3 phases][2]: tile visits, raw edges examined
   int w_lds_doubles; // LDS room for W
@@ -179,11 +181,12 @@ __global__ void k_weights_node(double* W, int nx, int nz, int n_off, const int32
 
 // blockIdx.y = problem; x strides over its nodes
 __global__ void k_init_fields(const ProbDev* probs, const JobDev* jobs, int32_t* err,
-                              unsigned long long* stats) {
+                              unsigned long long* stats, int32_t* persist_result) {
   const ProbDev pr = probs[blockIdx.y];
   const int64_t n = (int64_t)jobs[pr.job].nx * jobs[pr.job].nz;
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 12) {
     if (threadIdx.x == 0) *err = 0;
+    if (threadIdx.x < 4) persist_result[threadIdx.x] = 0;
     stats[threadIdx.x] = 0ull;
   }
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
@@ -194,23 +197,27 @@ __global__ void k_init_fields(const ProbDev* probs, const JobDev* jobs, int32_t*
   }
 }
 
-__global__ void k_clear_flags(int32_t* flags, int64_t n_flags, int32_t* counter, int n_counter) {
+__global__ void k_clear_flags(int32_t* flags, int64_t n_flags, int32_t* counter, int n_counter,
+                              uint32_t* bar) {
   int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t t = tid; t < n_flags; t += (int64_t)gridDim.x * blockDim.x) flags[t] = 0;
   for (int64_t t = tid; t < n_counter; t += (int64_t)gridDim.x * blockDim.x) counter[t] = 0;
+  if (tid < 3) bar[tid] = 0u;  // barrier arrivals, generation, abort
 }
 
 // activate the source tile of every problem (t* phase: only problems with t*)
-__global__ void k_seed_flags(int32_t* flags, int32_t* counter, const ProbDev* probs,
-                             const JobDev* jobs, int n_prob, int tx, int tz, int tstar_phase) {
+__global__ void k_seed_flags(int32_t* flags, int32_t* list, int32_t* counter,
+                             const ProbDev* probs, const JobDev* jobs, int n_prob, int tx, int tz,
+                             int tstar_phase) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_prob) return;
   const ProbDev pr = probs[p];
   if (tstar_phase && pr.tstar == nullptr) return;
   const JobDev jb = jobs[pr.job];
   int sx = (int)(pr.src % jb.nx), sz = (int)(pr.src / jb.nx);
-  flags[pr.tile_base + (sz / tz) * jb.ntx + (sx / tx)] = kFlagActive | kFlagSeed;
-  atomicAdd(&counter[0], 1);
+  const int T = pr.tile_base + (sz / tz) * jb.ntx + (sx / tx);
+  flags[T] = kFlagActive | kFlagSeed;
+  list[atomicAdd(&counter[0], 1)] = T;
 }
 
 // --------------------------------------------------------- tile helpers ---
@@ -224,12 +231,11 @@ struct TileCtx {
 
 // Claim this workgroup's (problem, tile) for the round: find the problem by
 // binary search over the tile bases, read and clear the tile's flag.
-__device__ __forceinline__ TileCtx tile_begin(const RelaxArgs& a, int round, int* s_flag,
+__device__ __forceinline__ TileCtx tile_begin(const RelaxArgs& a, int round, int T, int* s_flag,
                                               int* s_prob) {
   // Plain round-robin order: the active tiles of a round form a compact
   // wavefront band, and dealing consecutive tiles to different XCDs spreads
   // that band over all of them (banding tiles per XCD measured slower).
-  const int T = blockIdx.x;
   int32_t* fin = a.flags + (int64_t)(round & 1) * a.n_tiles;
   if (threadIdx.x == 0) {
     int32_t f = fin[T];
@@ -287,7 +293,9 @@ __device__ __forceinline__ void activate(const RelaxArgs& a, int round, const Ti
     if (nx_ < 0 || nx_ >= jb.ntx || nz_ < 0 || nz_ >= jb.ntz) continue;
     int32_t* f = &fout[pr.tile_base + nz_ * jb.ntx + nx_];
     const int32_t bits = (bit == 4) ? (kFlagActive | kFlagFull) : kFlagActive;
-    if (atomicOr(f, bits) == 0) atomicAdd(&a.counter[round + 1], 1);
+    if (atomicOr(f, bits) == 0)
+      a.list[(int64_t)((round + 1) & 1) * a.n_tiles + atomicAdd(&a.counter[round + 1], 1)] =
+          pr.tile_base + nz_ * jb.ntx + nx_;
   }
 }
 
@@ -426,16 +434,15 @@ __device__ __forceinline__ int my_node(const RelaxArgs& a, const TileCtx& c) {
 
 // Phase TAU: tau_j <- min(tau_j, tau_i + w_ij) (eq 31).
 template <int G>
-__global__ void __launch_bounds__(kRelaxThreads) k_relax_tau(RelaxArgs a, int round) {
+__device__ __forceinline__ void relax_tau(const RelaxArgs& a, int round, int T) {
   extern __shared__ double smem_d[];
   __shared__ int s_flag, s_prob, s_mask, s_cnt[3];
-  const TileCtx c = tile_begin(a, round, &s_flag, &s_prob);
+  const TileCtx c = tile_begin(a, round, T, &s_flag, &s_prob);
   if (!c.active) return;
   const Smem s = carve(a, smem_d);
   const int R = a.R, lw = a.lw, n = lw * a.lh, n_off = a.n_off;
   const ProbDev pr = a.probs[c.p];
   const JobDev jb = a.jobs[pr.job];
-  const int K = jb.K;
   if (threadIdx.x == 0) {
     s_mask = 0;
     s_cnt[0] = 0;
@@ -560,16 +567,15 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_tau(RelaxArgs a, int ro
 
 // Phase HOP: BFS hop counts over tight edges, h_j <- min(h_j, h_i + 1).
 template <int G>
-__global__ void __launch_bounds__(kRelaxThreads) k_relax_hop(RelaxArgs a, int round) {
+__device__ __forceinline__ void relax_hop(const RelaxArgs& a, int round, int T) {
   extern __shared__ double smem_d[];
   __shared__ int s_flag, s_prob, s_mask, s_cnt[3];
-  const TileCtx c = tile_begin(a, round, &s_flag, &s_prob);
+  const TileCtx c = tile_begin(a, round, T, &s_flag, &s_prob);
   if (!c.active) return;
   const Smem s = carve(a, smem_d);
   const int R = a.R, lw = a.lw, n = lw * a.lh, n_off = a.n_off;
   const ProbDev pr = a.probs[c.p];
   const JobDev jb = a.jobs[pr.job];
-  const int K = jb.K;
   if (threadIdx.x == 0) {
     s_mask = 0;
     s_cnt[0] = 0;
@@ -753,17 +759,16 @@ __global__ void k_pred_offsets(RelaxArgs a) {
 // node whose value became known pushes to the children naming it as their
 // predecessor.
 template <int G>
-__global__ void __launch_bounds__(kRelaxThreads) k_relax_tstar(RelaxArgs a, int round) {
+__device__ __forceinline__ void relax_tstar(const RelaxArgs& a, int round, int T) {
   extern __shared__ double smem_d[];
   __shared__ int s_flag, s_prob, s_mask, s_cnt[3];
-  const TileCtx c = tile_begin(a, round, &s_flag, &s_prob);
+  const TileCtx c = tile_begin(a, round, T, &s_flag, &s_prob);
   if (!c.active) return;
   const Smem s = carve(a, smem_d);
   const int R = a.R, lw = a.lw, n = lw * a.lh, n_off = a.n_off;
   const ProbDev pr = a.probs[c.p];
   if (!pr.tstar) return;  // block-uniform
   const JobDev jb = a.jobs[pr.job];
-  const int K = jb.K;
   if (threadIdx.x == 0) {
     s_mask = 0;
     s_cnt[0] = 0;
@@ -876,6 +881,96 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_tstar(RelaxArgs a, int 
   if (threadIdx.x == 0 && s_mask) activate(a, round, c, pr, jb, s_mask);
 }
 
+// One launch per round: one workgroup per tile of every problem.
+template <int G>
+__global__ void __launch_bounds__(kRelaxThreads) k_relax_tau(RelaxArgs a, int round) {
+  relax_tau<G>(a, round, blockIdx.x);
+}
+template <int G>
+__global__ void __launch_bounds__(kRelaxThreads) k_relax_hop(RelaxArgs a, int round) {
+  relax_hop<G>(a, round, blockIdx.x);
+}
+template <int G>
+__global__ void __launch_bounds__(kRelaxThreads) k_relax_tstar(RelaxArgs a, int round) {
+  relax_tstar<G>(a, round, blockIdx.x);
+}
+
+// ------------------------------------------------- persistent launch ---
+// All rounds of a phase in one launch: a grid no larger than the device
+// holds at once walks each round's active-tile list, and rounds are
+// separated by a device-wide barrier.  The barrier's wait is bounded: a
+// workgroup that waits longer than kBarrierWaitTicks (or sees another's
+// abort) raises the abort word and leaves, so every wave exits.
+
+constexpr uint64_t kBarrierWaitTicks = 200000000ull;  // 2 s of the 100 MHz real-time clock
+
+struct PersistArgs {
+  int max_rounds;
+  uint32_t* bar;    // [0] arrivals, [1] generation, [2] abort
+  int32_t* result;  // [phase]: rounds to convergence, -1 cap reached, -2 aborted
+};
+
+// Device-wide barrier; false if aborted.  Release before arriving and
+// acquire after leaving, at agent scope (the L2s of the XCDs are not
+// coherent with each other for plain accesses).
+__device__ __forceinline__ bool grid_barrier(const PersistArgs& p) {
+  __shared__ int s_ok;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const uint32_t gen =
+        __hip_atomic_load(&p.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t arrived =
+        __hip_atomic_fetch_add(&p.bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == gridDim.x - 1) {
+      __hip_atomic_store(&p.bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&p.bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const uint64_t t0 = wall_clock64();
+      while (__hip_atomic_load(&p.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        if (__hip_atomic_load(&p.bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+            wall_clock64() - t0 > kBarrierWaitTicks) {
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    if (!ok) __hip_atomic_store(&p.bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_ok = ok;
+  }
+  __syncthreads();
+  __threadfence();
+  return s_ok != 0;
+}
+
+template <int G, int PH>
+__global__ void __launch_bounds__(kRelaxThreads) k_relax_persist(RelaxArgs a, PersistArgs p) {
+  for (int round = 0; round < p.max_rounds; ++round) {
+    const int n_act =
+        __hip_atomic_load(&a.counter[round], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t* lst = a.list + (int64_t)(round & 1) * a.n_tiles;
+    for (int i = blockIdx.x; i < n_act; i += gridDim.x) {
+      const int T = lst[i];
+      if constexpr (PH == 0) relax_tau<G>(a, round, T);
+      else if constexpr (PH == 1) relax_hop<G>(a, round, T);
+      else relax_tstar<G>(a, round, T);
+      __syncthreads();  // LDS is reused by the next tile
+    }
+    if (!grid_barrier(p)) {
+      if (threadIdx.x == 0) p.result[PH] = -2;
+      return;
+    }
+    if (__hip_atomic_load(&a.counter[round + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+        0) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) p.result[PH] = round + 1;
+      return;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) p.result[PH] = -1;
+}
+
 // unreachable nodes: t* = +inf.  blockIdx.y = problem.
 __global__ void k_tstar_finish(const ProbDev* probs, const JobDev* jobs) {
   const ProbDev pr = probs[blockIdx.y];
@@ -909,7 +1004,8 @@ struct Plan {
   int max_rounds = 0;
   std::vector<int64_t> nodes;  // per job
   std::vector<int> ntx, ntz, K;
-  size_t off_star = 0, off_lbin = 0, off_jobs = 0, off_probs = 0, off_flags = 0, off_counter = 0,
+  size_t off_star = 0, off_lbin = 0, off_jobs = 0, off_probs = 0, off_flags = 0, off_list = 0,
+         off_counter = 0,
          off_err = 0, off_hop = 0, total = 0;
   std::vector<size_t> off_W;  // per job
   int w_lds_doubles = 0;
@@ -953,7 +1049,8 @@ static int validate_opts(const chert_trace_opts* o) {
   if (!o) return fail(CHERT_ERR_INVALID_ARG, "null options");
   if (o->push_group != 0 && o->push_group != 1 && o->push_group != 2 && o->push_group != 4)
     return fail(CHERT_ERR_INVALID_ARG, "push_group must be 0, 1, 2 or 4");
-  if (o->reserved != 0) return fail(CHERT_ERR_INVALID_ARG, "reserved must be 0");
+  if (o->launch != CHERT_LAUNCH_PER_ROUND && o->launch != CHERT_LAUNCH_PERSISTENT)
+    return fail(CHERT_ERR_INVALID_ARG, "launch must be CHERT_LAUNCH_PER_ROUND or _PERSISTENT");
   uint32_t outs = o->outputs;
   if (outs == 0 || (outs & ~31u)) return fail(CHERT_ERR_INVALID_ARG, "bad output mask");
   if ((outs & CHERT_OUT_TSTAR) && !((outs & CHERT_OUT_TAU_R) && (outs & CHERT_OUT_PRED_P)))
@@ -1019,6 +1116,8 @@ static int make_plan(const chert_trace_job* jobs, int n_jobs, const chert_trace_
   off += align256((size_t)P->n_prob * sizeof(ProbDev));
   P->off_flags = off;
   off += align256((size_t)2 * P->n_tiles * sizeof(int32_t));
+  P->off_list = off;
+  off += align256((size_t)2 * P->n_tiles * sizeof(int32_t));
   P->off_counter = off;
   off += align256((size_t)(P->max_rounds + 2) * sizeof(int32_t));
   P->off_err = off;
@@ -1059,9 +1158,60 @@ static int run_rounds(hipStream_t s, const RelaxArgs& a, void (*kern)(RelaxArgs,
   return fail(CHERT_ERR_NO_CONVERGENCE, "relaxation round cap reached");
 }
 
-static int trace_batch(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o,
-                       void* workspace_dev, size_t workspace_bytes, hipStream_t s) {
+typedef void (*RoundKern)(RelaxArgs, int);
+typedef void (*PersistKern)(RelaxArgs, PersistArgs);
+
+static RoundKern round_kernel(int ph, int G) {
+  if (ph == 0) return G == 1 ? k_relax_tau<1> : (G == 2 ? k_relax_tau<2> : k_relax_tau<4>);
+  if (ph == 1) return G == 1 ? k_relax_hop<1> : (G == 2 ? k_relax_hop<2> : k_relax_hop<4>);
+  return G == 1 ? k_relax_tstar<1> : (G == 2 ? k_relax_tstar<2> : k_relax_tstar<4>);
+}
+
+static PersistKern persist_kernel(int ph, int G) {
+  if (ph == 0)
+    return G == 1 ? k_relax_persist<1, 0> : (G == 2 ? k_relax_persist<2, 0> : k_relax_persist<4, 0>);
+  if (ph == 1)
+    return G == 1 ? k_relax_persist<1, 1> : (G == 2 ? k_relax_persist<2, 1> : k_relax_persist<4, 1>);
+  return G == 1 ? k_relax_persist<1, 2> : (G == 2 ? k_relax_persist<2, 2> : k_relax_persist<4, 2>);
+}
+
+// Persistent-launch grid: as many workgroups as the device holds at once
+// (never more than the tiles), so every workgroup of the launch is resident.
+static int persist_grid(const void* kern, size_t lds, int64_t n_tiles, int* grid) {
+  int per_cu = 0, cus = 0, dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kRelaxThreads, lds);
+  if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+  if (per_cu < 1) return fail(CHERT_ERR_HIP, "relaxation kernel does not fit on a compute unit");
+  int64_t g = (int64_t)per_cu * cus;
+  if (g > n_tiles) g = n_tiles;
+  *grid = (int)(g < 1 ? 1 : g);
+  return CHERT_OK;
+}
+
+// A batch ready to run: plan, device tables uploaded, kernel arguments.
+struct Prepared {
   Plan P;
+  RelaxArgs a{};
+  PersistArgs pa{};
+  size_t lds = 0;
+  uint8_t* ws = nullptr;
+  JobDev* djobs = nullptr;
+  ProbDev* dprobs = nullptr;
+  std::vector<JobDev> jd;
+  int32_t* dox = nullptr;
+  int32_t* doz = nullptr;
+  double* dL = nullptr;
+  int32_t* dcol = nullptr;
+  int pgrid[3] = {0, 0, 0};  // persistent-launch grid per phase
+};
+
+// Plan the batch and upload its tables (synchronous on s).
+static int prepare(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o,
+                   void* workspace_dev, size_t workspace_bytes, hipStream_t s, Prepared* Q) {
+  Plan& P = Q->P;
   int rc = make_plan(jobs, n_jobs, o, &P);
   if (rc) return rc;
   if (!workspace_dev || workspace_bytes < P.total)
@@ -1100,7 +1250,8 @@ static int trace_batch(const chert_trace_job* jobs, int n_jobs, const chert_trac
   int32_t* dcol = dbin + (size_t)n_jobs * kMaxOffsets;
   (void)dbin;
 
-  std::vector<JobDev> jd(n_jobs);
+  std::vector<JobDev>& jd = Q->jd;
+  jd.assign(n_jobs, JobDev{});
   std::vector<ProbDev> probs;
   int32_t* hop = (int32_t*)(ws + P.off_hop);
   int64_t hop_off = 0;
@@ -1164,7 +1315,7 @@ static int trace_batch(const chert_trace_job* jobs, int n_jobs, const chert_trac
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // host buffers are locals
   if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
 
-  RelaxArgs a{};
+  RelaxArgs& a = Q->a;
   a.tx = P.tx;
   a.tz = P.tz;
   a.R = P.R;
@@ -1178,12 +1329,45 @@ static int trace_batch(const chert_trace_job* jobs, int n_jobs, const chert_trac
   a.ox = dox;
   a.oz = doz;
   a.flags = (int32_t*)(ws + P.off_flags);
+  a.list = (int32_t*)(ws + P.off_list);
   a.counter = (int32_t*)(ws + P.off_counter);
   a.err = (int32_t*)(ws + P.off_err);
   a.stats = (unsigned long long*)(ws + P.off_err + 64);
   a.w_lds_doubles = P.w_lds_doubles;
-  const size_t lds = lds_bytes(P.lw, P.lh, P.w_lds_doubles, P.n_off, P.tx, P.tz);
+  Q->lds = lds_bytes(P.lw, P.lh, P.w_lds_doubles, P.n_off, P.tx, P.tz);
+  Q->pa.max_rounds = P.max_rounds;
+  Q->pa.bar = (uint32_t*)(ws + P.off_err + 192);
+  Q->pa.result = (int32_t*)(ws + P.off_err + 208);
+  Q->ws = ws;
+  Q->djobs = djobs;
+  Q->dprobs = dprobs;
+  Q->dox = dox;
+  Q->doz = doz;
+  Q->dL = dL;
+  Q->dcol = dcol;
+  if (o->launch == CHERT_LAUNCH_PERSISTENT) {
+    const int G = o->push_group ? o->push_group : 2;
+    for (int ph = 0; ph < 3; ++ph) {
+      rc = persist_grid((const void*)persist_kernel(ph, G), Q->lds, P.n_tiles, &Q->pgrid[ph]);
+      if (rc) return rc;
+    }
+  }
+  return CHERT_OK;
+}
 
+
+// Enqueue every kernel of a prepared batch on s.  With the persistent
+// launch nothing here waits for the device, so the sequence can be captured
+// into a graph; the per-round launch synchronises s every 8 rounds to test
+// for termination.
+static int enqueue(const Prepared& Q, const chert_trace_job* jobs, int n_jobs,
+                   const chert_trace_opts* o, hipStream_t s, int rounds[3]) {
+  const Plan& P = Q.P;
+  const RelaxArgs& a = Q.a;
+  const PersistArgs& pa = Q.pa;
+  uint8_t* ws = Q.ws;
+  const uint32_t outs = o->outputs;
+  const size_t lds = Q.lds;
   for (int j = 0; j < n_jobs; ++j) {
     const chert_trace_job& J = jobs[j];
     chert_cache_layout lay;
@@ -1197,66 +1381,97 @@ static int trace_batch(const chert_trace_job* jobs, int n_jobs, const chert_trac
     const double* Vm = fields + CHERT_F_V * ent + mslice;
     const double* Am = fields + CHERT_F_A * ent + mslice;
     const int32_t* Sm = (const int32_t*)(cache + lay.status_offset) + mslice;
-    if (jd[j].per_node) {
+    if (Q.jd[j].per_node) {
       int64_t tw = P.nodes[j] * P.n_off;
       int64_t blocks = (tw + 255) / 256;
       CHERT_LAUNCH("k_weights_node", k_weights_node,
                    dim3((unsigned)(blocks > 65536 ? 65536 : blocks)), dim3(256), 0, s,
-                   (double*)(ws + P.off_W[j]), jd[j].nx, jd[j].nz, P.n_off, dox, doz,
-                   dL + (size_t)j * kMaxOffsets, dcol + (size_t)j * kMaxOffsets, n_cols, Vm,
+                   (double*)(ws + P.off_W[j]), Q.jd[j].nx, Q.jd[j].nz, P.n_off, Q.dox, Q.doz,
+                   Q.dL + (size_t)j * kMaxOffsets, Q.dcol + (size_t)j * kMaxOffsets, n_cols, Vm,
                    Am, Sm);
     } else {
       int64_t tw = 2 * K * K * P.n_off;
       int64_t blocks = (tw + 255) / 256;
       CHERT_LAUNCH("k_weights", k_weights, dim3((unsigned)(blocks > 65536 ? 65536 : blocks)),
                    dim3(256), 0, s, (double*)(ws + P.off_W[j]), (int)K, P.n_off, Vm, Am, Sm,
-                   n_cols, dL + (size_t)j * kMaxOffsets, dcol + (size_t)j * kMaxOffsets);
+                   n_cols, Q.dL + (size_t)j * kMaxOffsets, Q.dcol + (size_t)j * kMaxOffsets);
     }
   }
   int64_t max_nodes = 0;
   for (int64_t n : P.nodes) max_nodes = n > max_nodes ? n : max_nodes;
   const unsigned gx = (unsigned)((max_nodes + 255) / 256 > 1024 ? 1024 : (max_nodes + 255) / 256);
   const dim3 pgrid(gx, (unsigned)P.n_prob);
-  CHERT_LAUNCH("k_init_fields", k_init_fields, pgrid, dim3(256), 0, s, dprobs, djobs, a.err, a.stats);
+  CHERT_LAUNCH("k_init_fields", k_init_fields, pgrid, dim3(256), 0, s, Q.dprobs, Q.djobs, a.err,
+               a.stats, pa.result);
   const int64_t n_flags = 2 * P.n_tiles;
   auto init_flags = [&](int tstar_phase) {
-    CHERT_LAUNCH("k_clear_flags", k_clear_flags, dim3(256), dim3(256), 0, s, a.flags, n_flags, a.counter,
-                       P.max_rounds + 2);
-    CHERT_LAUNCH("k_seed_flags", k_seed_flags, dim3((P.n_prob + 63) / 64), dim3(64), 0, s, a.flags,
-                       a.counter, dprobs, djobs, P.n_prob, P.tx, P.tz, tstar_phase);
+    CHERT_LAUNCH("k_clear_flags", k_clear_flags, dim3(256), dim3(256), 0, s, a.flags, n_flags,
+                 a.counter, P.max_rounds + 2, pa.bar);
+    CHERT_LAUNCH("k_seed_flags", k_seed_flags, dim3((P.n_prob + 63) / 64), dim3(64), 0, s,
+                 a.flags, a.list, a.counter, Q.dprobs, Q.djobs, P.n_prob, P.tx, P.tz,
+                 tstar_phase);
   };
-  // push work-item grouping (template instance)
-  typedef void (*Kern)(RelaxArgs, int);
   const int G = o->push_group ? o->push_group : 2;
-  Kern ktau = G == 1 ? k_relax_tau<1> : (G == 2 ? k_relax_tau<2> : k_relax_tau<4>);
-  Kern khop = G == 1 ? k_relax_hop<1> : (G == 2 ? k_relax_hop<2> : k_relax_hop<4>);
-  Kern ktst = G == 1 ? k_relax_tstar<1> : (G == 2 ? k_relax_tstar<2> : k_relax_tstar<4>);
-  int rounds[3] = {0, 0, 0};
-  init_flags(0);
-  rc = run_rounds(s, a, ktau, "k_relax_tau", lds, P.max_rounds, &rounds[0]);
+  static const char* kname[3] = {"k_relax_tau", "k_relax_hop", "k_relax_tstar"};
+  static const char* pname[3] = {"k_relax_persist_tau", "k_relax_persist_hop",
+                                 "k_relax_persist_tstar"};
+  auto phase = [&](int ph) -> int {
+    init_flags(ph == 2 ? 1 : 0);
+    if (o->launch == CHERT_LAUNCH_PERSISTENT) {
+      CHERT_LAUNCH(pname[ph], persist_kernel(ph, G), dim3((unsigned)Q.pgrid[ph]),
+                   dim3(kRelaxThreads), lds, s, a, pa);
+      rounds[ph] = 0;  // read back by finish()
+      return CHERT_OK;
+    }
+    return run_rounds(s, a, round_kernel(ph, G), kname[ph], lds, P.max_rounds, &rounds[ph]);
+  };
+  int rc = phase(0);
   if (rc) return rc;
   if (outs & (CHERT_OUT_PRED_P | CHERT_OUT_PRED_A)) {
-    init_flags(0);
-    rc = run_rounds(s, a, khop, "k_relax_hop", lds, P.max_rounds, &rounds[1]);
+    rc = phase(1);
     if (rc) return rc;
     CHERT_LAUNCH("k_pred", k_pred, pgrid, dim3(256), 0, s, a);
     CHERT_LAUNCH("k_pred_offsets", k_pred_offsets, pgrid, dim3(256), 0, s, a);
   }
   if (outs & CHERT_OUT_TSTAR) {
-    init_flags(1);
-    rc = run_rounds(s, a, ktst, "k_relax_tstar", lds, P.max_rounds, &rounds[2]);
+    rc = phase(2);
     if (rc) return rc;
-    CHERT_LAUNCH("k_tstar_finish", k_tstar_finish, pgrid, dim3(256), 0, s, dprobs, djobs);
+    CHERT_LAUNCH("k_tstar_finish", k_tstar_finish, pgrid, dim3(256), 0, s, Q.dprobs, Q.djobs);
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+  return CHERT_OK;
+}
+
+// Wait for a batch enqueued on s and report its errors and counters.
+static int finish(const Prepared& Q, const chert_trace_opts* o, hipStream_t s, int rounds[3],
+                  chert_trace_stats* stats_host) {
+  const RelaxArgs& a = Q.a;
   int32_t herr = 0;
+  int32_t hres[4] = {0, 0, 0, 0};
   unsigned long long hstats[12];
-  e = hipMemcpyAsync(&herr, a.err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  hipError_t e = hipMemcpyAsync(&herr, a.err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(hstats, a.stats, sizeof(hstats), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hres, Q.pa.result, sizeof(hres), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
-  if (o->stats_host) {
-    chert_trace_stats* st = o->stats_host;
+  const uint32_t outs = o->outputs;
+  const bool ran[3] = {true, (outs & (CHERT_OUT_PRED_P | CHERT_OUT_PRED_A)) != 0,
+                       (outs & CHERT_OUT_TSTAR) != 0};
+  int status = CHERT_OK;
+  if (o->launch == CHERT_LAUNCH_PERSISTENT)
+    for (int ph = 0; ph < 3; ++ph) {
+      rounds[ph] = ran[ph] ? hres[ph] : 0;
+      if (ran[ph] && hres[ph] == -2 && !status)
+        status = fail(CHERT_ERR_HIP, "persistent relaxation: device-wide barrier timed out");
+      if (ran[ph] && hres[ph] == -1 && !status)
+        status = fail(CHERT_ERR_NO_CONVERGENCE, "relaxation round cap reached");
+      if (rounds[ph] < 0) rounds[ph] = Q.P.max_rounds;
+    }
+  if (stats_host) {
+    chert_trace_stats* st = stats_host;
     for (int ph = 0; ph < 3; ++ph) {
       st->rounds[ph] = rounds[ph];
       st->tile_visits[ph] = (int64_t)hstats[2 * ph];
@@ -1266,8 +1481,20 @@ static int trace_batch(const chert_trace_job* jobs, int n_jobs, const chert_trac
     }
     st->reserved = 0;
   }
+  if (status) return status;
   if (herr) return fail(CHERT_ERR_INVALID_ARG, "class id out of range");
   return CHERT_OK;
+}
+
+static int trace_batch(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o,
+                       void* workspace_dev, size_t workspace_bytes, hipStream_t s) {
+  Prepared Q;
+  int rc = prepare(jobs, n_jobs, o, workspace_dev, workspace_bytes, s, &Q);
+  if (rc) return rc;
+  int rounds[3] = {0, 0, 0};
+  rc = enqueue(Q, jobs, n_jobs, o, s, rounds);
+  if (rc) return rc;
+  return finish(Q, o, s, rounds, o->stats_host);
 }
 
 static chert_trace_job single_job(const chert_cache_desc* d, const void* cache_dev,
@@ -1334,4 +1561,154 @@ extern "C" int chert_trace_field(const chert_cache_desc* d, const void* cache_de
   chert_trace_job j = single_job(d, cache_dev, n_classes, g, mode, src_nodes_host, n_src,
                                  tau_r_dev, tau_i_dev, tstar_dev, pred_p_dev, pred_a_dev);
   return trace_batch(&j, 1, o, workspace_dev, workspace_bytes, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------- autotune --
+
+namespace {
+const int kTuneTiles[][2] = {{32, 32}, {64, 16}, {16, 64}, {32, 16}, {16, 32}, {128, 8}};
+const int kTuneGroups[] = {1, 2, 4};
+const int kTuneLaunch[] = {CHERT_LAUNCH_PER_ROUND, CHERT_LAUNCH_PERSISTENT};
+}  // namespace
+
+extern "C" size_t chert_trace_autotune_workspace_bytes(const chert_trace_job* jobs,
+                                                       int32_t n_jobs,
+                                                       const chert_trace_opts* o) {
+  if (!o) return 0;
+  size_t best = 0;
+  for (const auto& t : kTuneTiles) {
+    chert_trace_opts c = *o;
+    c.tile_x = t[0];
+    c.tile_z = t[1];
+    const size_t b = chert_trace_batch_workspace_bytes(jobs, n_jobs, &c);
+    if (b > best) best = b;
+  }
+  return best;
+}
+
+extern "C" int chert_trace_autotune(const chert_trace_job* jobs, int32_t n_jobs,
+                                    chert_trace_opts* o, void* workspace_dev,
+                                    size_t workspace_bytes, void* stream, double* best_ms) {
+  if (!o || !jobs || n_jobs < 1) return fail(CHERT_ERR_INVALID_ARG, "null options or jobs");
+  hipStream_t s = (hipStream_t)stream;
+  // probe: the first source of every job
+  std::vector<chert_trace_job> probe(jobs, jobs + n_jobs);
+  for (auto& j : probe) j.n_src = j.n_src > 0 ? 1 : 0;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(CHERT_ERR_HIP, "event creation failed");
+  double best = -1.0;
+  chert_trace_opts pick = *o;
+  int tried = 0;
+  for (const auto& t : kTuneTiles)
+    for (int G : kTuneGroups)
+      for (int L : kTuneLaunch) {
+        chert_trace_opts c = *o;
+        c.tile_x = t[0];
+        c.tile_z = t[1];
+        c.push_group = G;
+        c.launch = L;
+        c.stats_host = nullptr;
+        const size_t need = chert_trace_batch_workspace_bytes(probe.data(), n_jobs, &c);
+        if (need == 0 || need > workspace_bytes) continue;  // shape not valid here
+        int rc = CHERT_OK;
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && rc == CHERT_OK; ++rep) {  // second run is timed
+          (void)hipEventRecord(e0, s);
+          rc = trace_batch(probe.data(), n_jobs, &c, workspace_dev, workspace_bytes, s);
+          (void)hipEventRecord(e1, s);
+          if (hipEventSynchronize(e1) != hipSuccess) rc = CHERT_ERR_HIP;
+          if (rc == CHERT_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (rc != CHERT_OK) continue;
+        ++tried;
+        if (best < 0.0 || ms < best) {
+          best = ms;
+          pick = c;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (tried == 0) return fail(CHERT_ERR_INVALID_ARG, "no candidate fits the workspace");
+  o->tile_x = pick.tile_x;
+  o->tile_z = pick.tile_z;
+  o->push_group = pick.push_group;
+  o->launch = pick.launch;
+  if (best_ms) *best_ms = best;
+  return CHERT_OK;
+}
+
+// ---------------------------------------------------------------- graphs --
+
+struct chert_trace_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  chert::Prepared Q;
+  chert_trace_opts o{};
+};
+
+extern "C" int chert_trace_graph_create(const chert_trace_job* jobs, int32_t n_jobs,
+                                        const chert_trace_opts* o, void* workspace_dev,
+                                        size_t workspace_bytes, void* stream,
+                                        chert_trace_graph** out) {
+  if (!out) return fail(CHERT_ERR_INVALID_ARG, "null graph handle");
+  *out = nullptr;
+  if (!o || o->launch != CHERT_LAUNCH_PERSISTENT)
+    return fail(CHERT_ERR_INVALID_ARG, "graph capture needs the persistent launch");
+  if (!stream) return fail(CHERT_ERR_INVALID_ARG, "graph capture needs a non-null stream");
+  hipStream_t s = (hipStream_t)stream;
+  chert_trace_graph* G = new (std::nothrow) chert_trace_graph();
+  if (!G) return fail(CHERT_ERR_CAPACITY, "out of host memory");
+  int rc = chert::prepare(jobs, n_jobs, o, workspace_dev, workspace_bytes, s, &G->Q);
+  if (rc) {
+    delete G;
+    return rc;
+  }
+  G->o = *o;
+  G->o.stats_host = nullptr;
+  const bool prof = chert::prof_suspend();
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    chert::prof_resume(prof);
+    delete G;
+    return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+  }
+  int rounds[3];
+  rc = chert::enqueue(G->Q, jobs, n_jobs, &G->o, s, rounds);
+  e = hipStreamEndCapture(s, &G->graph);
+  chert::prof_resume(prof);
+  if (rc == CHERT_OK && e != hipSuccess) rc = fail(CHERT_ERR_HIP, hipGetErrorString(e));
+  if (rc == CHERT_OK) {
+    e = hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) rc = fail(CHERT_ERR_HIP, hipGetErrorString(e));
+  }
+  if (rc) {
+    if (G->graph) (void)hipGraphDestroy(G->graph);
+    delete G;
+    return rc;
+  }
+  *out = G;
+  return CHERT_OK;
+}
+
+extern "C" int chert_trace_graph_launch(chert_trace_graph* g, void* stream) {
+  if (!g) return fail(CHERT_ERR_INVALID_ARG, "null graph");
+  hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+  return CHERT_OK;
+}
+
+extern "C" int chert_trace_graph_finish(chert_trace_graph* g, void* stream,
+                                        chert_trace_stats* stats_host) {
+  if (!g) return fail(CHERT_ERR_INVALID_ARG, "null graph");
+  int rounds[3] = {0, 0, 0};
+  return chert::finish(g->Q, &g->o, (hipStream_t)stream, rounds, stats_host);
+}
+
+extern "C" int chert_trace_graph_destroy(chert_trace_graph* g) {
+  if (!g) return CHERT_OK;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return CHERT_OK;
 }

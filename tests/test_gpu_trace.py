@@ -51,7 +51,7 @@ def assert_fields_equal(g, o, s_idx=0):
         assert np.array_equal(a, b), (key, int(np.sum(a != b)))
 
 
-def imported_case(G, model, modes, tile=(0, 0), sources=None, n_sweep=1440):
+def imported_case(G, model, modes, tile=(0, 0), sources=None, n_sweep=1440, launch=0):
     cls, f, s = oracle_cache(model, modes, n_sweep)
     Cm = C()
     desc = Cm.cache_desc(n_dirs=model.n_dirs, modes=modes, n_sweep=n_sweep)
@@ -60,7 +60,8 @@ def imported_case(G, model, modes, tile=(0, 0), sources=None, n_sweep=1440):
     sources = model.sources if sources is None else sources
     for mode in modes:
         g = G.trace(cache, desc, K, model.nx, model.nz, model.hx, model.hz, model.radius,
-                    model.class_id, mode, sources, tile_x=tile[0], tile_z=tile[1])
+                    model.class_id, mode, sources, tile_x=tile[0], tile_z=tile[1],
+                    launch=launch)
         for si, src in enumerate(sources):
             o = O.trace_2d(model.nx, model.nz, model.hx, model.hz, model.class_id,
                            model.radius, f[0, mode], f[1, mode], s[mode], src)
@@ -68,9 +69,12 @@ def imported_case(G, model, modes, tile=(0, 0), sources=None, n_sweep=1440):
             assert_fields_equal(g, o, si)
 
 
-def test_imported_cache_small_layered_bitwise(G):
+@pytest.mark.parametrize("launch", [0, 1])
+def test_imported_cache_small_layered_bitwise(G, launch):
+    """Both launch forms (one launch per round; one persistent launch per
+    phase) reach the oracle's fields bitwise."""
     m = W.small_layered()
-    imported_case(G, m, (0, 1, 2))
+    imported_case(G, m, (0, 1, 2), launch=launch)
 
 
 @pytest.mark.parametrize("tile", [(8, 8), (16, 4), (32, 16), (64, 16)])
@@ -156,9 +160,9 @@ def test_invalid_class_id_reported(G):
     assert e.value.code == 1
 
 
-def test_batch_uneven_grids_modes_sources_bitwise(G):
-    """chert_trace_batch: two grids of different size and class count, two
-    modes each, several sources -> every field bitwise equal to the oracle."""
+def uneven_batch(G):
+    """Two grids of different size and class count, two modes each, several
+    sources, on imported oracle caches."""
     import torch
     Cm = C()
     m1 = W.small_layered(nx=61, nz=35, radius=3, seed=21)
@@ -183,11 +187,10 @@ def test_batch_uneven_grids_modes_sources_bitwise(G):
             b.add(desc, cache, K, grid, mode, srcs, **out)
             jobs.append((mdl, f, s, mode, srcs, out))
         keep += [cache, cid, grid, desc]
-    opts = Cm.trace_opts(Cm.OUT_ALL)
-    ws = torch.empty(Cm.chert_trace_batch_workspace_bytes(b, opts), dtype=torch.uint8,
-                     device=G.DEV)
-    Cm.chert_trace_batch(b, opts, ws)
-    torch.cuda.synchronize()
+    return b, jobs, keep
+
+
+def check_batch(jobs):
     for mdl, f, s, mode, srcs, out in jobs:
         g = {"tauR": out["tau_r"].cpu().numpy(), "tauI": out["tau_i"].cpu().numpy(),
              "tstar": out["tstar"].cpu().numpy(), "predP": out["pred_p"].cpu().numpy(),
@@ -196,6 +199,80 @@ def test_batch_uneven_grids_modes_sources_bitwise(G):
             o = O.trace_2d(mdl.nx, mdl.nz, mdl.hx, mdl.hz, mdl.class_id, mdl.radius,
                            f[0, mode], f[1, mode], s[mode], src)
             assert_fields_equal(g, o, si)
+
+
+@pytest.mark.parametrize("launch", [0, 1])
+def test_batch_uneven_grids_modes_sources_bitwise(G, launch):
+    """chert_trace_batch over uneven grids, modes and sources: every field
+    bitwise equal to the oracle, in both launch forms."""
+    Cm = C()
+    b, jobs, keep = uneven_batch(G)
+    stats = Cm.TraceStats()
+    opts = Cm.trace_opts(Cm.OUT_ALL, launch=launch, stats=stats)
+    ws = torch.empty(Cm.chert_trace_batch_workspace_bytes(b, opts), dtype=torch.uint8,
+                     device=G.DEV)
+    Cm.chert_trace_batch(b, opts, ws)
+    torch.cuda.synchronize()
+    print("launch", launch, stats.as_dict())
+    assert min(stats.rounds) > 0
+    check_batch(jobs)
+
+
+def test_graph_replays_match_eager(G):
+    """The batch captured as one graph: three replays, each after eager work
+    of the program's own and a wipe of the outputs, equal the eager
+    persistent run bitwise (and so the oracle)."""
+    Cm = C()
+    b, jobs, keep = uneven_batch(G)
+    opts = Cm.trace_opts(Cm.OUT_ALL, launch=Cm.LAUNCH_PERSISTENT)
+    ws = torch.empty(Cm.chert_trace_batch_workspace_bytes(b, opts), dtype=torch.uint8,
+                     device=G.DEV)
+    Cm.chert_trace_batch(b, opts, ws)
+    torch.cuda.synchronize()
+    eager = [{k: v.clone() for k, v in j[5].items()} for j in jobs]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        graph = Cm.TraceGraph(b, opts, ws, stream=stream)
+    try:
+        for rep in range(3):
+            x = torch.randn(256, 256, device=G.DEV)
+            y = (x @ x).sum()
+            torch.cuda.synchronize()
+            assert torch.isfinite(y)
+            for j in jobs:
+                for t in j[5].values():
+                    t.fill_(-7)
+            torch.cuda.synchronize()
+            graph.launch(stream)
+            stats = Cm.TraceStats()
+            graph.finish(stats, stream)
+            assert min(stats.rounds) > 0, stats.as_dict()
+            for j, ref in zip(jobs, eager):
+                for k, v in j[5].items():
+                    assert torch.equal(v, ref[k]), (rep, k)
+    finally:
+        graph.close()
+    check_batch(jobs)
+
+
+def test_autotuned_options_give_identical_fields(G):
+    """The autotuner picks one of its candidates; the full batch traced with
+    the picked options is still bitwise the oracle's."""
+    Cm = C()
+    b, jobs, keep = uneven_batch(G)
+    opts = Cm.trace_opts(Cm.OUT_ALL)
+    ws = torch.empty(Cm.chert_trace_autotune_workspace_bytes(b, opts), dtype=torch.uint8,
+                     device=G.DEV)
+    ms = Cm.chert_trace_autotune(b, opts, ws)
+    print("autotuned", opts.tile_x, opts.tile_z, opts.push_group, opts.launch, ms)
+    assert ms > 0 and opts.push_group in (1, 2, 4) and opts.launch in (0, 1)
+    assert opts.tile_x * opts.tile_z <= 1024
+    for j in jobs:
+        for t in j[5].values():
+            t.fill_(-3)
+    Cm.chert_trace_batch(b, opts, ws)
+    torch.cuda.synchronize()
+    check_batch(jobs)
 
 
 def test_per_node_trace_bitwise(G):
