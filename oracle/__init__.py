@@ -66,6 +66,10 @@ def lib():
         L.orc_trace_uncached_2d.argtypes = [l, l, d, d, P, P, i, i, i, i, i,
                                             i, l, P, P]
         L.orc_raypath.argtypes = [P, l, l, l, P, l, P]
+        L.orc_fibonacci.argtypes = [i, P]
+        L.orc_build_cache_3d.argtypes = [P, l, i, u, i, i, P, P]
+        L.orc_star_3d.argtypes = [i, d, d, d, i, P, P, P, P, P]
+        L.orc_trace_3d.argtypes = [l, l, l, d, d, d, P, i, i, P, P, P, l, P, P, P, P]
         _lib = L
     return _lib
 
@@ -223,3 +227,55 @@ def raypath(pred, src, rcv, capacity=None):
     if rc == 5:
         return rc, ln.value
     return rc, (path[: ln.value].copy() if rc == 0 else None)
+
+
+# --------------------------------------------------------------------- 3D --
+
+N_FIB = 41253
+
+
+def fibonacci(N=N_FIB):
+    """Fibonacci ray directions [N, 3] (x, y, z), z down."""
+    f = np.zeros((N, 3))
+    lib().orc_fibonacci(N, _p(f))
+    return f
+
+
+def build_cache_3d(classes, N=N_FIB, mode_mask=0b011, reading=MEV, n_sweep=N_SWEEP):
+    """(fields [NF][3][K][N], status [3][K][N]) on the Fibonacci directions,
+    each entry the sagittal-plane solve at the polar angle to the axis."""
+    classes = np.ascontiguousarray(np.atleast_2d(classes), dtype=np.float64)
+    K = classes.shape[0]
+    fields = np.full((NF, 3, K, N), np.nan)
+    status = np.zeros((3, K, N), dtype=np.int32)
+    rc = lib().orc_build_cache_3d(_p(classes), K, N, mode_mask, reading, n_sweep,
+                                  _p(fields), _p(status))
+    if rc:
+        raise ValueError(f"orc_build_cache_3d failed rc={rc}")
+    return fields, status
+
+
+def star_3d(R, hx, hy, hz, N=N_FIB):
+    n = lib().orc_star_3d(R, hx, hy, hz, N, None, None, None, None, None)
+    ox, oy, oz, b = (np.zeros(n, np.int32) for _ in range(4))
+    L = np.zeros(n)
+    lib().orc_star_3d(R, hx, hy, hz, N, _p(ox), _p(oy), _p(oz), _p(L), _p(b))
+    return ox, oy, oz, L, b
+
+
+def trace_3d(nx, ny, nz, hx, hy, hz, class_id, R, V, A, status, src, N=N_FIB):
+    """Dijkstra (tauR, tauI, predP, predA) on a 3D grid; node ix + nx (iy + ny iz)."""
+    n = nx * ny * nz
+    cid = np.ascontiguousarray(class_id, dtype=np.int32).reshape(-1)
+    assert cid.size == n
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    st = np.ascontiguousarray(status, dtype=np.int32)
+    out = {k: np.zeros(n) for k in ("tauR", "tauI")}
+    out.update({k: np.zeros(n, np.int32) for k in ("predP", "predA")})
+    rc = lib().orc_trace_3d(nx, ny, nz, hx, hy, hz, _p(cid), R, N, _p(V), _p(A), _p(st),
+                            int(src), _p(out["tauR"]), _p(out["tauI"]), _p(out["predP"]),
+                            _p(out["predA"]))
+    if rc:
+        raise ValueError(f"orc_trace_3d failed rc={rc}")
+    return out

@@ -702,6 +702,8 @@ typedef struct {
   long nx, nz;
   int n_off;
   const int32_t *ox, *oz, *bin;
+  long ny;              /* 1 in 2D */
+  const int32_t *oy;    /* NULL in 2D */
   const double *L;
   const int32_t *cls;   /* node -> class; NULL: the class is the node */
   int n_cols;           /* cache columns */
@@ -733,17 +735,24 @@ static double edge_weight(const graph_t *g, int field, long i, long j, int o) {
   return g->L[o] * abar;
 }
 
-/* neighbour j = i + o (in-grid) or -1 */
-static long step(const graph_t *g, long i, int o) {
-  long ix = i % g->nx, iz = i / g->nx;
-  long jx = ix + g->ox[o], jz = iz + g->oz[o];
-  if (jx < 0 || jx >= g->nx || jz < 0 || jz >= g->nz) return -1;
-  return jx + g->nx * jz;
+/* node index ix + nx (iy + ny iz): x fastest, then y, then z (2D: ny = 1) */
+static long node_at(const graph_t *g, long x, long y, long z) {
+  if (x < 0 || x >= g->nx || y < 0 || y >= g->ny || z < 0 || z >= g->nz) return -1;
+  return x + g->nx * (y + g->ny * z);
 }
+
+/* neighbour j = i + s o (s = +1 forward, -1 backward; in-grid) or -1 */
+static long step_dir(const graph_t *g, long i, int o, int s) {
+  long ix = i % g->nx, r = i / g->nx, iy = r % g->ny, iz = r / g->ny;
+  long dy = g->oy ? g->oy[o] : 0;
+  return node_at(g, ix + s * g->ox[o], iy + s * dy, iz + s * g->oz[o]);
+}
+
+static long step(const graph_t *g, long i, int o) { return step_dir(g, i, o, 1); }
 
 /* textbook Dijkstra with a binary heap and lazy deletion */
 static int dijkstra(const graph_t *g, int field, long src, double *tau) {
-  long n = g->nx * g->nz;
+  long n = g->nx * g->ny * g->nz;
   for (long i = 0; i < n; ++i) tau[i] = INFINITY;
   char *done = (char *)calloc((size_t)n, 1);
   heap_t h = {0, 0, 0};
@@ -777,7 +786,7 @@ static int dijkstra(const graph_t *g, int field, long src, double *tau) {
 static int predecessors(const graph_t *g, int field, long src,
                         const double *tau, int32_t *pred, int32_t *hop,
                         long *order, long *n_reached) {
-  long n = g->nx * g->nz;
+  long n = g->nx * g->ny * g->nz;
   for (long i = 0; i < n; ++i) {
     pred[i] = -1;
     hop[i] = -1;
@@ -804,11 +813,8 @@ static int predecessors(const graph_t *g, int field, long src,
     int best_o = -1;
     long best_i = -1;
     for (int o = 0; o < g->n_off; ++o) {
-      /* i = j - o */
-      long jx = j % g->nx, jz = j / g->nx;
-      long ix = jx - g->ox[o], iz = jz - g->oz[o];
-      if (ix < 0 || ix >= g->nx || iz < 0 || iz >= g->nz) continue;
-      long i = ix + g->nx * iz;
+      long i = step_dir(g, j, o, -1); /* i = j - o */
+      if (i < 0) continue;
       if (hop[i] < 0) continue;
       double w = edge_weight(g, field, i, j, o);
       if (!(tau[i] + w == tau[j])) continue;
@@ -864,8 +870,9 @@ int orc_trace_2d_cols(long nx, long nz, double hx, double hz,
   orc_star_2d(R, hx, hz, n_dirs, ox, oz, L, bin);
   for (int o = 0; o < n_off; ++o)
     if (col[bin[o]] < 0) { rc = 3; goto out; } /* cache lacks a star direction */
-  graph_t g = {nx, nz, n_off, ox, oz, bin, L, class_id,
-               subset ? n_subset : n_dirs, col, V, A, st};
+  graph_t g = {.nx = nx, .nz = nz, .n_off = n_off, .ox = ox, .oz = oz, .bin = bin,
+               .ny = 1, .oy = NULL, .L = L, .cls = class_id,
+               .n_cols = subset ? n_subset : n_dirs, .col = col, .V = V, .A = A, .st = st};
   long nrP = 0, nrA = 0;
   if (dijkstra(&g, 0, src, tR) || dijkstra(&g, 1, src, tI)) { rc = 2; goto out; }
   predecessors(&g, 0, src, tR, pP, hP, ordP, &nrP);
@@ -1014,4 +1021,187 @@ int orc_raypath(const int32_t *pred, long n_nodes, long src, long rcv,
     if (q > 0) cur = pred[cur];
   }
   return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 3D: Fibonacci ray directions, sagittal-plane cache (eqs 6, 35), 3D star  */
+/* ------------------------------------------------------------------------ */
+
+/* Readings for 3D (the paper gives the basis of eq 35 and the complex
+ * slowness direction of eq 6, not a 3D direction set):
+ *   - ray directions: the Fibonacci set f_i = (r cos phi_i, r sin phi_i, z_i),
+ *     z_i = 1 - (2i+1)/N, r = sqrt(1 - z_i^2), phi_i = i pi (3 - sqrt 5),
+ *     in global (x, y, z), z down; N = 41253 gives about one per square
+ *     degree;
+ *   - a TI class's axis is e_z' of eq 35; the solution whose ray direction is
+ *     f_i has its slowness in the plane of e_z' and f_i with zero imaginary
+ *     azimuth (the medium is symmetric about that plane), so entry i is the
+ *     2D sagittal solve (eq 7) at the local polar angle
+ *     alpha_i = arccos(f_i . e_z');
+ *   - entry i stores RX, RZ = the x and z components of f_i (its y component
+ *     is f_i's); there is no centrosymmetric copy (the set is not symmetric).
+ *   - node index ix + nx (iy + ny iz); star offsets with max norm <= R and
+ *     gcd(|ox|, |oy|, |oz|) = 1 ordered by (oy, oz, ox) ascending; length
+ *     sqrt((ox hx)^2 + (oz hz)^2 + (oy hy)^2) summed in that order; bin = the
+ *     i maximising f_i . o_hat (x, y, z order), ties to the lowest i. */
+
+void orc_fibonacci(int N, double *f) {
+  const double ga = ORC_PI * (3.0 - sqrt(5.0));
+  for (int i = 0; i < N; ++i) {
+    double z = 1.0 - (2.0 * i + 1.0) / N;
+    double r = sqrt(1.0 - z * z);
+    double ph = i * ga;
+    f[3 * i] = r * cos(ph);
+    f[3 * i + 1] = r * sin(ph);
+    f[3 * i + 2] = z;
+  }
+}
+
+/* symmetry axis e_z' of eq 35 */
+static void axis_3d(double tilt, double azimuth, double e[3]) {
+  e[0] = sin(tilt) * cos(azimuth);
+  e[1] = sin(tilt) * sin(azimuth);
+  e[2] = cos(tilt);
+}
+
+/* fields [ORC_NF][3][n_classes][N], status [3][n_classes][N] */
+int orc_build_cache_3d(const double *classes, long n_classes, int N,
+                       unsigned mode_mask, int reading, int n_sweep,
+                       double *fields, int32_t *status) {
+  if (N < 2 || n_sweep < 8) return 1;
+  double *f = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+  sample_t *tab = (sample_t *)malloc(sizeof(sample_t) * (size_t)n_sweep);
+  if (!f || !tab) { free(f); free(tab); return 2; }
+  orc_fibonacci(N, f);
+  long stride = 3L * n_classes * N;
+  for (int mode = 0; mode < 3; ++mode) {
+    if (!(mode_mask & (1u << mode))) continue;
+    for (long k = 0; k < n_classes; ++k) {
+      const double *cls = classes + 13 * k;
+      medium_t m;
+      load_medium(cls, &m);
+      long base = ((long)mode * n_classes + k) * N;
+      int fluid = (mode != ORC_QP) && (cls[3] == 0.0 || (mode == ORC_QSH && cls[4] == 0.0));
+      if (fluid) {
+        for (int i = 0; i < N; ++i) {
+          write_invalid(fields, stride, base + i);
+          status[base + i] = ORC_ST_FLUID;
+        }
+        continue;
+      }
+      double ax[3];
+      axis_3d(cls[11], cls[12], ax);
+      sweep(&m, mode, reading, n_sweep, tab);
+      for (int i = 0; i < N; ++i) {
+        double c = f[3 * i] * ax[0] + f[3 * i + 1] * ax[1] + f[3 * i + 2] * ax[2];
+        if (c > 1.0) c = 1.0;
+        if (c < -1.0) c = -1.0;
+        double alpha = acos(c);
+        entry_t e;
+        int st = solve_direction(&m, mode, reading, n_sweep, tab, alpha, &e);
+        long idx = base + i;
+        if (st & ORC_ST_NO_BRACKET) {
+          write_invalid(fields, stride, idx);
+          status[idx] = st;
+          continue;
+        }
+        if (!(e.A >= 0.0) || !isfinite(e.V) || !(e.V > 0.0)) st |= ORC_ST_NONPHYS;
+        fields[F_V * stride + idx] = e.V;
+        fields[F_A * stride + idx] = e.A;
+        fields[F_Q * stride + idx] = e.Q;
+        fields[F_RX * stride + idx] = f[3 * i];
+        fields[F_RZ * stride + idx] = f[3 * i + 2];
+        fields[F_THR * stride + idx] = e.thR;
+        fields[F_THI * stride + idx] = e.thI;
+        fields[F_RES * stride + idx] = e.res;
+        status[idx] = st;
+      }
+    }
+  }
+  free(f);
+  free(tab);
+  return 0;
+}
+
+static int gcd3(int a, int b, int c) { return gcd_int(gcd_int(a, b), c); }
+
+/* 3D star (see the readings above).  Returns the count; arrays may be NULL. */
+int orc_star_3d(int R, double hx, double hy, double hz, int N, int32_t *ox,
+                int32_t *oy, int32_t *oz, double *L, int32_t *bin) {
+  double *f = NULL;
+  if (ox) {
+    f = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+    if (!f) return -1;
+    orc_fibonacci(N, f);
+  }
+  int n = 0;
+  for (int y = -R; y <= R; ++y)
+    for (int z = -R; z <= R; ++z)
+      for (int x = -R; x <= R; ++x) {
+        if (x == 0 && y == 0 && z == 0) continue;
+        if (gcd3(x, y, z) != 1) continue;
+        if (ox) {
+          double dx = x * hx, dy = y * hy, dz = z * hz;
+          double len = sqrt(dx * dx + dz * dz + dy * dy);
+          double u0 = dx / len, u1 = dy / len, u2 = dz / len;
+          int best = 0;
+          double bd = -2.0;
+          for (int i = 0; i < N; ++i) {
+            double d = f[3 * i] * u0 + f[3 * i + 1] * u1 + f[3 * i + 2] * u2;
+            if (d > bd) { bd = d; best = i; }
+          }
+          ox[n] = x;
+          oy[n] = y;
+          oz[n] = z;
+          L[n] = len;
+          bin[n] = best;
+        }
+        ++n;
+      }
+  free(f);
+  return n;
+}
+
+/* Dijkstra traveltimes and predecessors on a 3D grid with a class cache
+ * on the Fibonacci directions (V, A, st: [n_classes][N] of one mode). */
+int orc_trace_3d(long nx, long ny, long nz, double hx, double hy, double hz,
+                 const int32_t *class_id, int R, int N, const double *V,
+                 const double *A, const int32_t *st, long src, double *tauR,
+                 double *tauI, int32_t *predP, int32_t *predA) {
+  long n = nx * ny * nz;
+  if (src < 0 || src >= n || R < 1) return 1;
+  int n_off = orc_star_3d(R, hx, hy, hz, N, NULL, NULL, NULL, NULL, NULL);
+  int32_t *ox = (int32_t *)malloc(sizeof(int32_t) * n_off);
+  int32_t *oy = (int32_t *)malloc(sizeof(int32_t) * n_off);
+  int32_t *oz = (int32_t *)malloc(sizeof(int32_t) * n_off);
+  int32_t *bin = (int32_t *)malloc(sizeof(int32_t) * n_off);
+  double *L = (double *)malloc(sizeof(double) * n_off);
+  int32_t *col = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+  double *t = (double *)malloc(sizeof(double) * (size_t)n);
+  int32_t *pr = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t *hp = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  long *ord = (long *)malloc(sizeof(long) * (size_t)n);
+  int rc = 0;
+  if (!ox || !oy || !oz || !bin || !L || !col || !t || !pr || !hp || !ord) { rc = 2; goto out; }
+  orc_star_3d(R, hx, hy, hz, N, ox, oy, oz, L, bin);
+  for (int i = 0; i < N; ++i) col[i] = i;
+  graph_t g = {.nx = nx, .nz = nz, .n_off = n_off, .ox = ox, .oz = oz, .bin = bin,
+               .ny = ny, .oy = oy, .L = L, .cls = class_id, .n_cols = N, .col = col,
+               .V = V, .A = A, .st = st};
+  for (int field = 0; field < 2; ++field) {
+    double *out_t = field ? tauI : tauR;
+    int32_t *out_p = field ? predA : predP;
+    if (!out_t && !out_p) continue;
+    if (dijkstra(&g, field, src, t)) { rc = 2; goto out; }
+    if (out_p) {
+      long nr = 0;
+      predecessors(&g, field, src, t, pr, hp, ord, &nr);
+      memcpy(out_p, pr, sizeof(int32_t) * (size_t)n);
+    }
+    if (out_t) memcpy(out_t, t, sizeof(double) * (size_t)n);
+  }
+out:
+  free(ox); free(oy); free(oz); free(bin); free(L); free(col);
+  free(t); free(pr); free(hp); free(ord);
+  return rc;
 }
