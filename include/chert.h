@@ -106,9 +106,19 @@ int chert_classes_from_thomsen(const double *params_dev, int64_t n,
  * direction; among several roots (triplications) the largest ray velocity
  * wins.  Entries d >= n_dirs/2 are the centrosymmetric copies of d - n_dirs/2.
  * ------------------------------------------------------------------------ */
+/* 3D caches (dim 3; eqs 6, 35): column i is the Fibonacci ray direction
+ *   f_i = (r cos phi_i, r sin phi_i, z_i), z_i = 1 - (2i+1)/n_dirs,
+ *   r = sqrt(1 - z_i^2), phi_i = i pi (3 - sqrt 5)   (global x, y, z; z down),
+ * n_dirs = 41253 giving about one direction per square degree.  For a TI
+ * class the ray direction f_i is reached with the slowness in the plane of
+ * the symmetry axis e_z' (eq 35: (sin t0 cos p0, sin t0 sin p0, cos t0) with
+ * t0 = tilt, p0 = azimuth) and f_i, imaginary azimuth 0; entry i is that
+ * sagittal-plane solve at the local polar angle arccos(f_i . e_z') with the
+ * same root search as in 2D.  Every column is solved (no centrosymmetric
+ * copies, no subsets); RX and RZ hold the x and z components of f_i. */
 typedef struct chert_cache_desc {
-  int32_t dim;        /* 2 (3 is reserved: UNSUPPORTED)                    */
-  int32_t n_dirs;     /* even, >= 4; 360 = 1 degree                         */
+  int32_t dim;        /* 2, or 3 (Fibonacci directions, see above)          */
+  int32_t n_dirs;     /* 2D: even, >= 4; 360 = 1 degree.  3D: 2..2^20      */
   uint32_t mode_mask; /* bit (1 << chert_mode) per mode to build            */
   int32_t kernel;     /* chert_kernel                                       */
   int32_t n_sweep;    /* theta_R sweep samples, >= 16 (1440 = 0.25 degree)  */
@@ -182,9 +192,16 @@ int chert_build_cache(const chert_cache_desc *d, const chert_class *classes_dev,
  * attenuation folded along the propagation raypath: t*_src = 0,
  * t*_j = t*_pred_p(j) + w_I(pred_p(j) -> j).
  * ------------------------------------------------------------------------ */
+/* 3D grids (dim 3): node index ix + nx (iy + ny iz); the star holds the
+ * offsets with max(|ox|, |oy|, |oz|) <= radius (1..4) and gcd 1, ordered by
+ * (oy, oz, ox) ascending, L_o = sqrt((ox hx)^2 + (oz hz)^2 + (oy hy)^2), and
+ * the bin of o is the Fibonacci direction with the largest dot product with
+ * o / L_o (lowest index on ties).  3D traces give tau_R and tau_I (with a
+ * class map and a 3D cache); the relaxation is a node-frontier
+ * label-correcting iteration with the same fixed point. */
 typedef struct chert_grid {
-  int32_t dim;                 /* 2 (3 is reserved: UNSUPPORTED)           */
-  int32_t radius;              /* forward-star radius R, 1..8              */
+  int32_t dim;                 /* 2 or 3                                   */
+  int32_t radius;              /* forward-star radius R, 1..8 (3D: 1..4)   */
   int64_t nx, nz, ny;          /* nodes per axis; ny must be 1 in 2D       */
   double hx, hz, hy;           /* node spacing [m]                         */
   const int32_t *class_id_dev; /* [n_nodes] class of each node, in range   */
@@ -338,6 +355,11 @@ int chert_extract_raypath(const int32_t *pred_host, int64_t n_nodes,
  * arrays may be NULL to count only. */
 int chert_star_2d(int32_t radius, double hx, double hz, int32_t n_dirs,
                   int32_t *ox, int32_t *oz, double *len, int32_t *bin);
+
+/* The 3D star of a grid (see chert_grid) with the bins of an n_dirs
+ * Fibonacci cache (host, synchronous; returns the count or -1). */
+int chert_star_3d(int32_t radius, double hx, double hy, double hz, int32_t n_dirs,
+                  int32_t *ox, int32_t *oy, int32_t *oz, double *len, int32_t *bin);
 
 /* ------------------------------------------------------------------------
  * Learned surrogate of the cache solve (an addition to the paper's method,

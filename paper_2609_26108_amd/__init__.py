@@ -42,6 +42,7 @@ EXPORTS = (
     "chert_build_cache_surrogate_workspace_bytes", "chert_build_cache_surrogate",
     "chert_trace_graph_create", "chert_trace_graph_launch", "chert_trace_graph_finish",
     "chert_trace_graph_destroy", "chert_trace_autotune_workspace_bytes", "chert_trace_autotune",
+    "chert_star_3d",
 )
 WARM_NSTATS = 10
 # parameter blocks of the surrogate, in their order in the parameter vector
@@ -183,6 +184,7 @@ def lib():
         L.chert_trace_autotune_workspace_bytes.argtypes = [P, i32, P]
         L.chert_trace_autotune_workspace_bytes.restype = sz
         L.chert_trace_autotune.argtypes = [P, i32, P, P, sz, P, P]
+        L.chert_star_3d.argtypes = [i32, d, d, d, i32, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -261,6 +263,26 @@ def chert_star_2d(radius, hx, hz, n_dirs=360):
     lib().chert_star_2d(radius, hx, hz, n_dirs, ox.ctypes.data, oz.ctypes.data,
                         L.ctypes.data, b.ctypes.data)
     return ox, oz, L, b
+
+
+def chert_star_3d(radius, hx, hy, hz, n_dirs=41253):
+    """(ox, oy, oz, length, bin) of the 3D forward star (host)."""
+    n = lib().chert_star_3d(radius, hx, hy, hz, n_dirs, None, None, None, None, None)
+    if n < 0:
+        _check(1)
+    ox, oy, oz, b = (np.zeros(n, np.int32) for _ in range(4))
+    L = np.zeros(n)
+    p = lambda a: ctypes.c_void_p(a.ctypes.data)
+    lib().chert_star_3d(radius, hx, hy, hz, n_dirs, p(ox), p(oy), p(oz), p(L), p(b))
+    return ox, oy, oz, L, b
+
+
+def make_grid3(nx, ny, nz, h, radius, class_id_dev, hy=None, hz=None):
+    """3D grid: node ix + nx (iy + ny iz), spacing h (or hx=h, hy, hz)."""
+    g = Grid(3, radius, nx, nz, ny, h, h if hz is None else hz, h if hy is None else hy,
+             class_id_dev.data_ptr())
+    g._keep = class_id_dev
+    return g
 
 
 def chert_extract_raypath(pred, src, rcv, capacity=None):

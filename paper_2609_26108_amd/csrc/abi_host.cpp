@@ -55,6 +55,54 @@ int star_2d(int R, double hx, double hz, int n_dirs, int32_t* ox, int32_t* oz, d
   return n;
 }
 
+void fibonacci(int N, double* f) {
+  const double ga = M_PI * (3.0 - sqrt(5.0));
+  for (int i = 0; i < N; ++i) {
+    const double z = 1.0 - (2.0 * i + 1.0) / N;
+    const double r = sqrt(1.0 - z * z);
+    const double ph = i * ga;
+    f[3 * i] = r * cos(ph);
+    f[3 * i + 1] = r * sin(ph);
+    f[3 * i + 2] = z;
+  }
+}
+
+int star_3d(int R, double hx, double hy, double hz, int N, int32_t* ox, int32_t* oy, int32_t* oz,
+            double* L, int32_t* bin) {
+  std::vector<double> f;
+  if (ox) {
+    f.resize(3 * (size_t)N);
+    fibonacci(N, f.data());
+  }
+  int n = 0;
+  for (int y = -R; y <= R; ++y)
+    for (int z = -R; z <= R; ++z)
+      for (int x = -R; x <= R; ++x) {
+        if ((x == 0 && y == 0 && z == 0) || gcd_i(gcd_i(x, y), z) != 1) continue;
+        if (ox) {
+          const double dx = x * hx, dy = y * hy, dz = z * hz;
+          const double len = sqrt(dx * dx + dz * dz + dy * dy);  // eq 27 in 3D
+          const double u0 = dx / len, u1 = dy / len, u2 = dz / len;
+          int best = 0;
+          double bd = -2.0;
+          for (int i = 0; i < N; ++i) {  // nearest tabulated direction
+            const double dd = f[3 * i] * u0 + f[3 * i + 1] * u1 + f[3 * i + 2] * u2;
+            if (dd > bd) {
+              bd = dd;
+              best = i;
+            }
+          }
+          ox[n] = x;
+          oy[n] = y;
+          oz[n] = z;
+          L[n] = len;
+          bin[n] = best;
+        }
+        ++n;
+      }
+  return n;
+}
+
 // ------------------------------------------------------------ profiling --
 
 struct ProfRec {
@@ -224,9 +272,15 @@ extern "C" int chert_classes_from_thomsen(const double* params_dev, int64_t n,
 extern "C" int chert_cache_layout_of(const chert_cache_desc* d, int64_t n_classes,
                                      chert_cache_layout* out) {
   if (!d || !out) return fail(CHERT_ERR_INVALID_ARG, "null desc or output");
-  if (d->dim == 3) return fail(CHERT_ERR_UNSUPPORTED, "3D caches are not built yet");
-  if (d->dim != 2) return fail(CHERT_ERR_INVALID_ARG, "dim must be 2");
-  if (d->n_dirs < 4 || (d->n_dirs & 1)) return fail(CHERT_ERR_INVALID_ARG, "n_dirs must be even, >= 4");
+  if (d->dim != 2 && d->dim != 3) return fail(CHERT_ERR_INVALID_ARG, "dim must be 2 or 3");
+  if (d->dim == 3) {
+    if (d->n_dirs < 2 || d->n_dirs > kMaxFibonacci)
+      return fail(CHERT_ERR_INVALID_ARG, "3D n_dirs (Fibonacci directions) must be 2..1048576");
+    if (d->n_subset != 0)
+      return fail(CHERT_ERR_UNSUPPORTED, "3D caches hold every direction (no subset)");
+  } else if (d->n_dirs < 4 || (d->n_dirs & 1)) {
+    return fail(CHERT_ERR_INVALID_ARG, "n_dirs must be even, >= 4");
+  }
   if ((d->mode_mask & ~7u) != 0) return fail(CHERT_ERR_INVALID_ARG, "bad mode mask");
   if (d->kernel != CHERT_KERNEL_MEV && d->kernel != CHERT_KERNEL_OEV)
     return fail(CHERT_ERR_INVALID_ARG, "bad kernel");
@@ -258,6 +312,20 @@ extern "C" int chert_cache_layout_of(const chert_cache_desc* d, int64_t n_classe
   size_t end = out->status_offset + entries * sizeof(int32_t);
   out->total_bytes = (end + 255) & ~(size_t)255;
   return CHERT_OK;
+}
+
+extern "C" int chert_star_3d(int32_t radius, double hx, double hy, double hz, int32_t n_dirs,
+                             int32_t* ox, int32_t* oy, int32_t* oz, double* len, int32_t* bin) {
+  if (radius < 1 || radius > kMaxRadius3 || !(hx > 0.0) || !(hy > 0.0) || !(hz > 0.0) ||
+      n_dirs < 2 || n_dirs > kMaxFibonacci) {
+    fail(CHERT_ERR_INVALID_ARG, "bad star arguments");
+    return -1;
+  }
+  if (ox && (!oy || !oz || !len || !bin)) {
+    fail(CHERT_ERR_INVALID_ARG, "star arrays must all be given");
+    return -1;
+  }
+  return star_3d(radius, hx, hy, hz, n_dirs, ox, oy, oz, len, bin);
 }
 
 extern "C" int chert_star_2d(int32_t radius, double hx, double hz, int32_t n_dirs,

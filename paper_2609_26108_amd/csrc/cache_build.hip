@@ -82,6 +82,8 @@ struct SolveArgs {
   int32_t* status;  // [3][n_classes][n_cols]
   int n_cols;       // stored direction columns per (mode, class)
   int n_solve;      // directions solved per (mode, class); the rest are copies
+  int dim;          // 2, or 3: columns are Fibonacci ray directions
+  double fib_ga;    // 3D: golden angle pi (3 - sqrt 5) of the direction set
   int subset;       // 0: every direction d < n_dirs/2, column d, copy at d + n_dirs/2
   int16_t dir[kMaxSubset / 2];   // solved direction (subset caches)
   int16_t col[kMaxSubset / 2];   // its column
@@ -98,6 +100,30 @@ __device__ __forceinline__ void dir_cols(const SolveArgs& a, int s, int* d, int*
     *c = a.col[s];
     *pc = a.pcol[s];
   }
+}
+
+// local target ray angle of 2D direction d (eq 36)
+__device__ __forceinline__ double dir_psi(const SolveArgs& a, int d, double tilt) {
+  return wrap_pi(d * (kTwoPi / a.n_dirs) - tilt);
+}
+
+// 3D: Fibonacci ray direction s of n_dirs, and its polar angle to the
+// symmetry axis e_z' of eq 35 (the target angle of the sagittal solve)
+__device__ __forceinline__ double3 fib_dir(const SolveArgs& a, int s) {
+  const double z = 1.0 - (2.0 * s + 1.0) / a.n_dirs;
+  const double r = sqrt(1.0 - z * z);
+  double sp, cp;
+  sincos(s * a.fib_ga, &sp, &cp);
+  return make_double3(r * cp, r * sp, z);
+}
+
+__device__ __forceinline__ double polar_to_axis(const double3& f, const chert_class& c) {
+  double st, ct, sa, ca;
+  sincos(c.tilt, &st, &ct);
+  sincos(c.azimuth, &sa, &ca);
+  double d = f.x * (st * ca) + f.y * (st * sa) + f.z * ct;
+  d = fmin(1.0, fmax(-1.0, d));
+  return acos(d);
 }
 
 // Newton on F = (h, psi - psi*) from the bracket interpolant.  Elastic modes
@@ -250,9 +276,9 @@ __device__ __forceinline__ bool is_bracket(const double2* tab, int j, int n, dou
 // LDS.  Lanes of a wavefront run it in step (brackets first, then the
 // refinements together); `br` is this lane's kMaxBr bracket slots in LDS.
 __device__ __forceinline__ int32_t solve_dir(const SolveArgs& a, const Medium& m, int mode,
-                                             const double2* tab, int d, int* br, Entry* best) {
+                                             const double2* tab, double psi_star, int* br,
+                                             Entry* best) {
   const bool el = theta_i_zero(m, mode);
-  const double psi_star = wrap_pi(d * (kTwoPi / a.n_dirs) - m.tilt);
   // phase 1: every sign change of the ray-direction miss over the sweep
   int nbr = 0;
   for (int j = 0; j < a.n_sweep; ++j) {
@@ -300,6 +326,26 @@ __device__ __forceinline__ void store_pair(const SolveArgs& a, int64_t row, int 
   a.fields[CHERT_F_RZ * stride + row + pcol] = -a.fields[CHERT_F_RZ * stride + row + col];
 }
 
+// 3D entry: one column per Fibonacci direction (no centrosymmetric copy);
+// the stored ray direction is the direction itself (x and z components)
+__device__ __forceinline__ void store_single(const SolveArgs& a, int64_t idx, int64_t stride,
+                                             const Entry& best, const double3& f, int32_t st) {
+  if (st & (CHERT_ST_NO_BRACKET | CHERT_ST_FLUID) || (st == CHERT_ST_NONPHYS && isnan(best.V))) {
+    store_invalid(a, idx, stride, st);
+    return;
+  }
+  double* fl = a.fields;
+  fl[CHERT_F_V * stride + idx] = best.V;
+  fl[CHERT_F_A * stride + idx] = best.A;
+  fl[CHERT_F_Q * stride + idx] = best.Q;
+  fl[CHERT_F_RX * stride + idx] = f.x;
+  fl[CHERT_F_RZ * stride + idx] = f.z;
+  fl[CHERT_F_THR * stride + idx] = best.thR;
+  fl[CHERT_F_THI * stride + idx] = best.thI;
+  fl[CHERT_F_RES * stride + idx] = best.res;
+  a.status[idx] = st;
+}
+
 // Entries of a class that cannot be solved (invalid parameters, or a shear
 // mode without shear stiffness).
 __device__ __forceinline__ int32_t class_block(const chert_class& c, int mode) {
@@ -324,19 +370,29 @@ __global__ void __launch_bounds__(64) k_solve(SolveArgs a) {
 
   const int sidx = chunk * 64 + threadIdx.x;
   if (sidx >= a.n_solve) return;
-  int d, col, pcol;
-  dir_cols(a, sidx, &d, &col, &pcol);
   const int64_t row = ((int64_t)mode * a.n_classes + k) * a.n_cols;
   const chert_class c = a.classes[k];
   Entry best{};
   best.V = NAN;
   int32_t st = class_block(c, mode);
+  if (a.dim == 3) {
+    const double3 f = fib_dir(a, sidx);
+    const int64_t stride = 3 * a.n_classes * (int64_t)a.n_cols;
+    if (!st) {
+      const Medium m = load_medium(c);
+      st = solve_dir(a, m, mode, tab, polar_to_axis(f, c), s_br + threadIdx.x * kMaxBr, &best);
+    }
+    store_single(a, row + sidx, stride, best, f, st);
+    return;
+  }
+  int d, col, pcol;
+  dir_cols(a, sidx, &d, &col, &pcol);
   if (st) {
     store_pair(a, row, col, pcol, best, 0.0, st);
     return;
   }
   const Medium m = load_medium(c);
-  st = solve_dir(a, m, mode, tab, d, s_br + threadIdx.x * kMaxBr, &best);
+  st = solve_dir(a, m, mode, tab, dir_psi(a, d, m.tilt), s_br + threadIdx.x * kMaxBr, &best);
   store_pair(a, row, col, pcol, best, m.tilt, st);
 }
 
@@ -384,7 +440,8 @@ __global__ void __launch_bounds__(kNodeThreads) k_build_fused(SolveArgs a, const
       int d, col, pcol;
       dir_cols(a, sidx, &d, &col, &pcol);
       Entry best{};
-      const int32_t st = solve_dir(a, m, mode, tab, d, s_br + threadIdx.x * kMaxBr, &best);
+      const int32_t st = solve_dir(a, m, mode, tab, dir_psi(a, d, m.tilt),
+                                   s_br + threadIdx.x * kMaxBr, &best);
       store_pair(a, row, col, pcol, best, m.tilt, st);
     }
   }
@@ -413,10 +470,6 @@ struct WarmArgs {
   unsigned long long* stats;    // CHERT_WARM_NSTATS counters
   double resid_tol;
 };
-
-__device__ __forceinline__ double dir_psi(const SolveArgs& a, int d, double tilt) {
-  return wrap_pi(d * (kTwoPi / a.n_dirs) - tilt);
-}
 
 // surrogate predictions for every (job, solved direction): 32 per workgroup
 __global__ void __launch_bounds__(mlp::kThreads) k_warm_predict(WarmArgs w, int64_t n_rows) {
@@ -731,7 +784,8 @@ __global__ void __launch_bounds__(64) k_warm_solve(WarmArgs w) {
         int d, col, pcol;
         dir_cols(a, s_flag[f], &d, &col, &pcol);
         Entry best{};
-        const int32_t st = solve_dir(a, m, mode, tab, d, s_br + lane * kMaxBr, &best);
+        const int32_t st = solve_dir(a, m, mode, tab, dir_psi(a, d, m.tilt), s_br + lane * kMaxBr,
+                                     &best);
         store_pair(a, row, col, pcol, best, m.tilt, st);
       }
     }
@@ -801,7 +855,13 @@ static SolveArgs solve_args(const chert_cache_desc* d, const chert_class* classe
   so.fields = cache ? (double*)(cache + lay.fields_offset) : nullptr;
   so.status = cache ? (int32_t*)(cache + lay.status_offset) : nullptr;
   const int half = d->n_dirs / 2;
-  if (d->n_subset == 0) {
+  so.dim = d->dim;
+  so.fib_ga = M_PI * (3.0 - sqrt(5.0));
+  if (d->dim == 3) {
+    so.subset = 0;
+    so.n_cols = d->n_dirs;
+    so.n_solve = d->n_dirs;
+  } else if (d->n_subset == 0) {
     so.subset = 0;
     so.n_cols = d->n_dirs;
     so.n_solve = half;
@@ -844,7 +904,7 @@ static int launch_status() {
 extern "C" size_t chert_build_cache_workspace_bytes(const chert_cache_desc* d,
                                                     int64_t n_classes) {
   if (!d || n_classes <= 0 || d->n_sweep <= 0) return 0;
-  if (n_jobs_of(d, n_classes) >= kFusedJobs) return 0;  // sweep table stays in LDS
+  if (d->dim != 3 && n_jobs_of(d, n_classes) >= kFusedJobs) return 0;  // table stays in LDS
   return (size_t)n_jobs_of(d, n_classes) * (size_t)d->n_sweep * sizeof(double2);
 }
 
@@ -864,7 +924,7 @@ extern "C" int chert_build_cache(const chert_cache_desc* d, const chert_class* c
   CHERT_LAUNCH("k_write_header", k_write_header, dim3(1), dim3(64), 0, s, cache, d->dim,
                d->n_dirs, d->mode_mask, d->kernel, d->n_sweep, d->n_subset, n_classes);
   const int64_t jobs = (int64_t)so.n_modes * n_classes;
-  if (jobs >= kFusedJobs) {
+  if (jobs >= kFusedJobs && d->dim != 3) {
     CHERT_LAUNCH("k_build_fused", k_build_fused, dim3((unsigned)jobs), dim3(kNodeThreads),
                  (size_t)d->n_sweep * sizeof(double2), s, so, (const int32_t*)nullptr,
                  (const int32_t*)nullptr, jobs);
@@ -882,6 +942,7 @@ extern "C" int chert_build_cache(const chert_cache_desc* d, const chert_class* c
     if (blocks > 65536) blocks = 65536;
     CHERT_LAUNCH("k_sweep", k_sweep, dim3((unsigned)blocks), dim3(256), 0, s, sa);
     const int chunks = (so.n_solve + 63) / 64;
+    if (jobs * chunks > 0x7fffffffLL) return fail(CHERT_ERR_INVALID_ARG, "too many entries");
     CHERT_LAUNCH("k_solve", k_solve, dim3((unsigned)(jobs * chunks)), dim3(64),
                  (size_t)d->n_sweep * sizeof(double2), s, so);
   }
@@ -910,6 +971,8 @@ extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
   chert_cache_layout lay;
   int rc = common_checks(d, classes_dev, n_classes, cache_dev, &lay);
   if (rc != CHERT_OK) return rc;
+  if (d->dim == 3)
+    return fail(CHERT_ERR_UNSUPPORTED, "surrogate-started builds are 2D (3D: chert_build_cache)");
   if (!blob_dev || ((uintptr_t)blob_dev & 255u))
     return fail(CHERT_ERR_INVALID_ARG, "null or unaligned surrogate blob");
   if (!(resid_tol >= 0.0)) return fail(CHERT_ERR_INVALID_ARG, "negative residual tolerance");

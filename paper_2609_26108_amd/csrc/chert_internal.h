@@ -16,6 +16,9 @@ constexpr int kMaxSweep = 4096;  // sweep table staged in LDS: 64 KiB
 constexpr int kMaxRadius = 8;
 constexpr int kMaxSubset = 512;  // direction columns of a subset cache
 constexpr int kMaxOffsets = 288;  // (2R+1)^2 - 1 bound on |O_R| in 2D for R <= 8
+constexpr int kMaxRadius3 = 4;    // 3D star radius limit
+constexpr int kMaxOffsets3 = 728; // (2R+1)^3 - 1 bound on |O_R| in 3D for R <= 4
+constexpr int kMaxFibonacci = 1 << 20;
 
 // Record a failure message for chert_last_error() and return the code.
 int fail(int code, const char* msg);
@@ -24,6 +27,13 @@ int fail(int code, const char* msg);
 // only), lengths and direction bins.  Returns the count.
 int star_2d(int R, double hx, double hz, int n_dirs, int32_t* ox, int32_t* oz, double* L,
             int32_t* bin);
+
+// Fibonacci ray directions f[3 N] (x, y, z) and the 3D forward star: offsets
+// with max norm <= R, gcd 1, ordered by (oy, oz, ox); lengths; bins = the
+// nearest Fibonacci direction (largest dot product, lowest index on ties).
+void fibonacci(int N, double* f);
+int star_3d(int R, double hx, double hy, double hz, int N, int32_t* ox, int32_t* oy, int32_t* oz,
+            double* L, int32_t* bin);
 
 // Kernel timing for chert_prof_*: returns a slot (or -1 when profiling is
 // off) after recording a start event on the stream; prof_end records the stop.

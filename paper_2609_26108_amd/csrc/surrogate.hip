@@ -406,6 +406,7 @@ extern "C" int chert_surrogate_dataset(const chert_cache_desc* d, const void* ca
   if (rc) return rc;
   if (!cache_dev || !classes_dev || !x_dev || !y_dev || !ok_dev)
     return fail(CHERT_ERR_INVALID_ARG, "null pointer");
+  if (d->dim != 2) return fail(CHERT_ERR_UNSUPPORTED, "training samples come from 2D caches");
   DatasetArgs a{};
   a.classes = classes_dev;
   a.n_classes = n_classes;

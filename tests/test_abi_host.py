@@ -69,9 +69,26 @@ def test_layout():
                 C.CacheDesc(2, 360, 1, 5, 1440, 0)]:
         with pytest.raises(C.ChertError):
             C.chert_cache_layout_of(bad, 5)
+    # 3D: every Fibonacci direction is a column; subsets are not supported
+    d3 = C.cache_desc(dim=3, n_dirs=41253, modes=(0, 1))
+    lay3 = C.chert_cache_layout_of(d3, 6)
+    assert lay3.status_offset == 256 + 8 * (3 * 6 * 41253) * 8
     with pytest.raises(C.ChertError) as e:
-        C.chert_cache_layout_of(C.cache_desc(dim=3), 5)
+        C.chert_cache_layout_of(C.cache_desc(dim=3, n_dirs=360, subset=[0, 180]), 5)
     assert e.value.code == 2
+    with pytest.raises(C.ChertError) as e:
+        C.chert_cache_layout_of(C.cache_desc(dim=4), 5)
+    assert e.value.code == 1
+
+
+def test_star_3d_matches_oracle():
+    """The library's host 3D star (offsets, lengths, Fibonacci bins) is the
+    oracle's, bitwise."""
+    for args in ((3, 10.0, 10.0, 10.0), (2, 10.0, 12.0, 8.0)):
+        a = C.chert_star_3d(*args)
+        b = O.star_3d(*args)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
 
 
 def test_raypath_matches_oracle_and_errors():
@@ -148,9 +165,18 @@ def test_device_calls_validate_before_launch():
     with pytest.raises(C.ChertError):  # t* without its inputs
         C.chert_trace_field(d, _FakeTensor(), 3, g, 0, [0], o2, workspace_dev=_FakeTensor(), stream=0)
     g3 = C.Grid(3, 3, 10, 10, 10, 5.0, 5.0, 5.0, 1234)
-    with pytest.raises(C.ChertError) as e:
+    with pytest.raises(C.ChertError) as e:  # 3D grid, 2D cache
         C.chert_trace_field(d, _FakeTensor(), 3, g3, 0, [0], o, workspace_dev=_FakeTensor(), stream=0)
+    assert e.value.code == 1
+    d3 = C.cache_desc(dim=3, n_dirs=41253, modes=(0, 1))
+    with pytest.raises(C.ChertError) as e:  # 3D: predecessors and t* not traced
+        C.chert_trace_field(d3, _FakeTensor(), 3, g3, 0, [0], o, workspace_dev=_FakeTensor(),
+                            stream=0)
     assert e.value.code == 2
+    o3 = C.trace_opts(C.OUT_TAU_R | C.OUT_TAU_I)
+    assert C.chert_trace_workspace_bytes(d3, 3, g3, 1, o3) > 0
+    g3b = C.Grid(3, 5, 10, 10, 10, 5.0, 5.0, 5.0, 1234)
+    assert C.chert_trace_workspace_bytes(d3, 3, g3b, 1, o3) == 0  # radius above 4
     assert C.chert_trace_workspace_bytes(d, 3, g, 1, o) > 0
 
 

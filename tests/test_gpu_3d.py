@@ -1,0 +1,164 @@
+"""GPU parity of the 3D path: Fibonacci-direction caches (sagittal
+reduction) against the oracle, and 3D node-frontier traveltimes against
+the oracle's 3D Dijkstra (bitwise on an imported cache, 1e-9 end to end)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+import workloads as W  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import chert_gpu
+    return chert_gpu
+
+
+def C():
+    import paper_2609_26108_amd as mod
+    return mod
+
+
+def model_classes(m):
+    return np.stack([O.class_from_thomsen(*L.thomsen_args()) for L in m.layers])
+
+
+def test_cache_3d_matches_oracle(G, rock_table):
+    """Every entry of a small Fibonacci cache (300 directions), tilted and
+    azimuthally rotated classes, all three modes."""
+    from test_gpu_cache import compare_cache
+    Cm = C()
+    cls = []
+    for i, r in enumerate(rock_table[:2]):
+        c = O.class_from_moduli(*(r[:5] * 1e6), *r[5:10], tilt=[0.3, -0.7][i],
+                                azimuth=[1.2, 4.0][i])
+        cls.append(c)
+    cls += list(model_classes(W.config5(nx=8, ny=8, nz=8, n_interfaces=1)))
+    cls = np.stack(cls)
+    N = 300
+    desc = Cm.cache_desc(dim=3, n_dirs=N, modes=(0, 1, 2), n_sweep=720)
+    cache = G.build_cache(G.classes_from_arrays(cls), desc)
+    fg, sg = G.cache_to_numpy(cache, desc, cls.shape[0])
+    fo, so = O.build_cache_3d(cls, N=N, mode_mask=0b111, n_sweep=720)
+    st = compare_cache(fg, sg, fo, so, (0, 1, 2))
+    print("3D cache", st)
+
+
+def test_cache_3d_full_direction_set_sampled(G):
+    """The full 41,253-direction cache of the 3D layered model (6 classes,
+    qP and qSV): sampled entries against single oracle solves at the polar
+    angle of the direction to the class's axis."""
+    Cm = C()
+    m = W.config5(nx=8, ny=8, nz=8)
+    cls = model_classes(m)
+    N = O.N_FIB
+    desc = Cm.cache_desc(dim=3, n_dirs=N, modes=(0, 1))
+    cache = G.build_cache(G.classes_from_arrays(cls), desc)
+    fg, sg = G.cache_to_numpy(cache, desc, cls.shape[0])
+    fib = O.fibonacci(N)
+    rng = np.random.default_rng(55)
+    checked = 0
+    for _ in range(40):
+        k = int(rng.integers(cls.shape[0]))
+        mode = int(rng.integers(2))
+        i = int(rng.integers(N))
+        t0, p0 = cls[k, 11], cls[k, 12]
+        ez = np.array([np.sin(t0) * np.cos(p0), np.sin(t0) * np.sin(p0), np.cos(t0)])
+        alpha = np.arccos(np.clip(fib[i] @ ez, -1, 1))
+        f, st = O.solve(cls[k], mode, alpha)
+        assert sg[mode, k, i] == st, (k, mode, i)
+        if st & (O.ST_NO_BRACKET | O.ST_FLUID):
+            continue
+        for name in ("V", "A", "Q"):
+            assert abs(fg[O.FIELDS.index(name), mode, k, i] - f[name]) <= 1e-10 * abs(f[name])
+        for name in ("thR", "thI"):
+            d = fg[O.FIELDS.index(name), mode, k, i] - f[name]
+            assert abs((d + np.pi) % (2 * np.pi) - np.pi) <= 1e-10
+        assert fg[3, mode, k, i] == pytest.approx(fib[i, 0], abs=1e-15)
+        assert fg[4, mode, k, i] == pytest.approx(fib[i, 2], abs=1e-15)
+        checked += 1
+    assert checked >= 30
+
+
+@pytest.fixture(scope="module")
+def small3d():
+    """A small 3D layered model (23 x 19 x 15 at 10 m, 4 layers, radius 3)
+    with its oracle cache on 400 Fibonacci directions."""
+    m = W.config5(nx=23, ny=19, nz=15, n_interfaces=3, radius=3,
+                  sources=((5, 5, 0), (17, 11, 0), (11, 9, 14)))
+    cls = model_classes(m)
+    f, s = O.build_cache_3d(cls, N=400, mode_mask=0b011, n_sweep=360)
+    return m, cls, f, s
+
+
+def trace3(G, m, cache, desc, K, mode):
+    Cm = C()
+    cid = torch.from_numpy(np.ascontiguousarray(m.class_id.reshape(-1), dtype=np.int32)).to(G.DEV)
+    g = Cm.make_grid3(m.nx, m.ny, m.nz, m.h, m.radius, cid)
+    stats = Cm.TraceStats()
+    o = Cm.trace_opts(Cm.OUT_TAU_R | Cm.OUT_TAU_I, stats=stats)
+    S, n = len(m.sources), m.n_nodes
+    tr = torch.empty((S, n), dtype=torch.float64, device=G.DEV)
+    ti = torch.empty((S, n), dtype=torch.float64, device=G.DEV)
+    ws = torch.empty(Cm.chert_trace_workspace_bytes(desc, K, g, S, o), dtype=torch.uint8,
+                     device=G.DEV)
+    Cm.chert_trace_field(desc, cache, K, g, mode, m.sources, o, tr, ti, None, None, None, ws)
+    torch.cuda.synchronize()
+    return tr.cpu().numpy(), ti.cpu().numpy(), stats.as_dict()
+
+
+def test_trace_3d_imported_cache_bitwise(G, small3d):
+    """On the oracle's cache, every 3D traveltime (three sources, two modes,
+    tau_R and tau_I) equals the oracle's Dijkstra bitwise."""
+    Cm = C()
+    m, cls, f, s = small3d
+    K = cls.shape[0]
+    desc = Cm.cache_desc(dim=3, n_dirs=400, modes=(0, 1), n_sweep=360)
+    cache = G.import_cache(f, s, desc, K)
+    for mode in (0, 1):
+        tr, ti, st = trace3(G, m, cache, desc, K, mode)
+        print("mode", mode, st)
+        for si, src in enumerate(m.sources):
+            o = O.trace_3d(m.nx, m.ny, m.nz, m.h, m.h, m.h, m.class_id, m.radius, f[0, mode],
+                           f[1, mode], s[mode], src, N=400)
+            assert np.array_equal(tr[si], o["tauR"]), (mode, si, int(np.sum(tr[si] != o["tauR"])))
+            assert np.array_equal(ti[si], o["tauI"]), (mode, si)
+
+
+def test_trace_3d_end_to_end(G, small3d):
+    """GPU cache -> GPU 3D trace against oracle cache -> oracle Dijkstra:
+    1e-9 relative."""
+    Cm = C()
+    m, cls, f, s = small3d
+    K = cls.shape[0]
+    desc = Cm.cache_desc(dim=3, n_dirs=400, modes=(0, 1), n_sweep=360)
+    cache = G.build_cache(G.classes_from_arrays(cls), desc)
+    for mode in (0, 1):
+        tr, ti, _ = trace3(G, m, cache, desc, K, mode)
+        o = O.trace_3d(m.nx, m.ny, m.nz, m.h, m.h, m.h, m.class_id, m.radius, f[0, mode],
+                       f[1, mode], s[mode], m.sources[0], N=400)
+        for a, b in ((tr[0], o["tauR"]), (ti[0], o["tauI"])):
+            fin = np.isfinite(b)
+            assert np.array_equal(np.isfinite(a), fin)
+            rel = np.abs(a[fin] - b[fin]) / np.maximum(np.abs(b[fin]), 1e-300)
+            assert rel.max() <= 1e-9, rel.max()
+
+
+def test_trace_3d_invalid_class_id_reported(G, small3d):
+    Cm = C()
+    m, cls, f, s = small3d
+    K = cls.shape[0]
+    desc = Cm.cache_desc(dim=3, n_dirs=400, modes=(0, 1), n_sweep=360)
+    cache = G.import_cache(f, s, desc, K)
+    bad = m.class_id.copy()
+    bad[7, 5, 5] = K + 3
+    m2 = W.Model3D(m.name, m.nx, m.ny, m.nz, m.h, m.layers, bad, m.sources, m.modes, m.radius)
+    with pytest.raises(Cm.ChertError) as e:
+        trace3(G, m2, cache, desc, K, 0)
+    assert e.value.code == 1

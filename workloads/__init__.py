@@ -292,3 +292,52 @@ def kmeans_classes(model, K, seed=0, max_iter=100):
     if (~solid).any():
         crow = np.concatenate([crow, rows[~solid].mean(0, keepdims=True)])
     return crow, cid.reshape(model.nz, model.nx)
+
+
+@dataclass
+class Model3D:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    h: float
+    layers: List[Layer]
+    class_id: np.ndarray          # int32 [nz, ny, nx]
+    sources: List[int]            # ix + nx (iy + ny iz)
+    modes: tuple
+    radius: int
+    n_dirs: int = 41253
+
+    @property
+    def n_nodes(self):
+        return self.nx * self.ny * self.nz
+
+
+def config5(nx=201, ny=201, nz=101, h=10.0, seed=None, n_interfaces=5, radius=3,
+            sources=((50, 50, 0), (150, 50, 0), (50, 150, 0), (150, 150, 0))):
+    """3D layered TTI: planar interfaces dipping up to 15 degrees with
+    uniform strike, spread over the depth; per-layer parameters as in the
+    layered 2D model plus an azimuth U[0, 360) deg; qP/qSV, radius 3, four
+    surface sources (ix, iy, iz)."""
+    rng = np.random.default_rng(seed_for(5) if seed is None else seed)
+    layers = []
+    for _ in range(n_interfaces + 1):
+        L = _layer_params(rng)
+        L.azimuth = math.radians(rng.uniform(0.0, 360.0))
+        layers.append(L)
+    x = np.arange(nx) * h
+    y = np.arange(ny) * h
+    z = np.arange(nz) * h
+    X, Y = np.meshgrid(x, y)                      # [ny, nx]
+    depth = (nz - 1) * h
+    cid = np.zeros((nz, ny, nx), np.int32)
+    for k in range(n_interfaces):
+        z0 = (k + 1) * depth / (n_interfaces + 1)
+        dip = math.radians(rng.uniform(0.0, 15.0))
+        strike = math.radians(rng.uniform(0.0, 360.0))
+        zi = z0 + math.tan(dip) * (math.cos(strike) * (X - x.mean()) +
+                                   math.sin(strike) * (Y - y.mean()))
+        cid += (z[:, None, None] > zi[None, :, :]).astype(np.int32)
+    src = [ix + nx * (iy + ny * iz) for ix, iy, iz in sources]
+    return Model3D(f"config5_3d_layered_{nx}x{ny}x{nz}", nx, ny, nz, h, layers, cid, src,
+                   (QP, QSV), radius)
