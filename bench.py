@@ -77,7 +77,10 @@ def parse():
     p.add_argument("--tile", type=int, nargs=2, default=(0, 0), metavar=("TX", "TZ"),
                    help="relaxation tile shape (0 0 = library default)")
     p.add_argument("--push-group", type=int, default=0, help="offsets per push item (1, 2, 4)")
-    p.add_argument("--workload", choices=("layered", "complex2d", "shots"), default="layered",
+    p.add_argument("--launch", type=int, default=0,
+                   help="relaxation launch: 0 one launch per round, 1 persistent")
+    p.add_argument("--workload", choices=("layered", "complex2d", "shots", "3d"),
+                   default="layered",
                    help="layered: the 5-layer model (default, the headline line); "
                         "complex2d: per-node caches of the structurally complex model, "
                         "plain vs surrogate-started; shots: 128 shots over 4 uneven "
@@ -119,6 +122,9 @@ def main():
     if args.workload == "shots":
         run_shots(args)
         return
+    if args.workload == "3d":
+        run_3d(args)
+        return
     if args.copy_calibration:
         # a plain copy of known size: FETCH_SIZE/WRITE_SIZE per dispatch of
         # this kernel against its true byte count gives the counter scale
@@ -143,7 +149,7 @@ def main():
     grid = C.make_grid(m.nx, m.nz, m.hx, m.hz, m.radius, cid)
     stats = C.TraceStats()
     opts = C.trace_opts(C.OUT_ALL, tile_x=args.tile[0], tile_z=args.tile[1], stats=stats,
-                        push_group=args.push_group)
+                        push_group=args.push_group, launch=args.launch)
     S = len(m.sources)
     n = m.n_nodes
     outs = {mode: dict(
@@ -230,7 +236,9 @@ def main():
     # algorithmic work is FP64 VALU: one add and one compare per useful edge
     # relaxation; peak = 78.6 TFLOP/s (FMA counted twice) / 2 = 39.3 T ops/s.
     if dom.startswith("k_relax"):
-        phase = {"k_relax_tau": 0, "k_relax_hop": 1, "k_relax_tstar": 2}[dom]
+        phase = {"k_relax_tau": 0, "k_relax_hop": 1, "k_relax_tstar": 2,
+                 "k_relax_persist_tau": 0, "k_relax_persist_hop": 1,
+                 "k_relax_persist_tstar": 2}[dom]
         useful_phase = {0: edges_per_step, 1: edges_per_step, 2: E * len(m.modes)}[phase]
         per_launch_ops = 2.0 * useful_phase / kernels[dom]["launches_per_step"]
         achieved = per_launch_ops / (kernels[dom]["avg_us"] * 1e-6) / 1e12
@@ -634,6 +642,105 @@ def run_shots(args):
     res["unit"] = "shots/s ((source, mode) fields with tau_R + pred + t*, one graph replay)"
     res["higher_is_better"] = True
     print(json.dumps(res))
+
+
+def useful_edges_3d(nx, ny, nz, ox, oy, oz):
+    return int(sum((nx - abs(a)) * (ny - abs(b)) * (nz - abs(c)) for a, b, c in zip(ox, oy, oz)))
+
+
+def run_3d(args):
+    """3D layered TTI (201 x 201 x 101 at 10 m, 6 classes, qP/qSV): cache on
+    41,253 Fibonacci directions, then tau_R and tau_I for four sources and
+    both modes in one batch."""
+    import torch
+    import paper_2609_26108_amd as C
+    import workloads as W
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    m = W.config5()
+    K = len(m.layers)
+    cls = torch.from_numpy(np.stack([C.chert_class_from_thomsen(*L.thomsen_args()).as_array()
+                                     for L in m.layers])).to(dev)
+    desc = C.cache_desc(dim=3, n_dirs=m.n_dirs, modes=m.modes)
+    lay = C.chert_cache_layout_of(desc, K)
+    cache = torch.zeros(lay.total_bytes, dtype=torch.uint8, device=dev)
+    cws = torch.empty(C.chert_build_cache_workspace_bytes(desc, K), dtype=torch.uint8, device=dev)
+    cid = torch.from_numpy(m.class_id.reshape(-1).astype(np.int32)).to(dev)
+    grid = C.make_grid3(m.nx, m.ny, m.nz, m.h, m.radius, cid)
+    S, n = len(m.sources), m.n_nodes
+    stats = C.TraceStats()
+    opts = C.trace_opts(C.OUT_TAU_R | C.OUT_TAU_I, stats=stats)
+    outs = {mode: (torch.empty((S, n), dtype=torch.float64, device=dev),
+                   torch.empty((S, n), dtype=torch.float64, device=dev)) for mode in m.modes}
+    b = C.Batch()
+    for mode in m.modes:
+        b.add(desc, cache, K, grid, mode, m.sources, tau_r=outs[mode][0], tau_i=outs[mode][1])
+    tws = torch.empty(C.chert_trace_batch_workspace_bytes(b, opts), dtype=torch.uint8, device=dev)
+    ox, oy, oz, _, _ = C.chert_star_3d(m.radius, m.h, m.h, m.h, m.n_dirs)
+    E = useful_edges_3d(m.nx, m.ny, m.nz, ox, oy, oz)
+    times = {"build": [], "trace": []}
+    for rep in range(1 + max(args.steps // 10, 1)):
+        ev = _events(torch, stream)
+        C.chert_build_cache(desc, cls, K, cache, cws, stream=stream)
+        tb = _elapsed(torch, ev, stream)
+        ev = _events(torch, stream)
+        C.chert_trace_batch(b, opts, tws, stream=stream)
+        tt = _elapsed(torch, ev, stream)
+        if rep > 0:  # the first pass warms up
+            times["build"].append(tb)
+            times["trace"].append(tt)
+    tb, tt = float(np.mean(times["build"])), float(np.mean(times["trace"]))
+    st = C.cache_views(cache, desc, K)[1]
+    conv = _converged(st[list(m.modes)].cpu().numpy())
+    fields = 2 * len(m.modes) * S
+    far = outs[m.modes[0]][0][0, -1].item()
+    if not np.isfinite(far):
+        raise RuntimeError("3D bench produced an unreachable far corner")
+    res = {"metric": METRIC, "workload": "3d", "n_gpus": 1, "dtype": "f64",
+           "data": "synthetic (seeded workloads.config5)",
+           "config": {"workload": "3D layered TTI 201x201x101 @10 m, 6 classes, qP/qSV, "
+                                  "41,253 Fibonacci directions, radius 3 (290 offsets), 4 sources",
+                      "nodes": n, "offsets": len(ox), "fields": fields},
+           "cache_build_s": tb, "hamiltonian_solves_per_s": conv / tb, "converged_entries": conv,
+           "trace_s": tt, "useful_edges_per_field": E,
+           "useful_edge_relaxations_per_s": E * fields / tt,
+           "raw_over_useful": stats.edge_relaxations[0] / (E * fields),
+           "iterations": stats.rounds[0], "repeats": len(times["trace"]),
+           "ms_per_step": 1e3 * (tb + tt)}
+    res["value"] = res["useful_edge_relaxations_per_s"]
+    res["unit"] = "useful edge relaxations/s (3D trace, 16 fields)"
+    res["higher_is_better"] = True
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline_3d(m)
+    print(json.dumps(res))
+
+
+def cpu_baseline_3d(m):
+    """The CPU oracle as it stands on a bounded sample of the 3D workload:
+    its cache build for one class and mode on 200 directions, and its
+    Dijkstra for one field on a 41 x 41 x 21 corner of the grid."""
+    import oracle as O
+    O.build(force=False)
+    cls = np.stack([O.class_from_thomsen(*L.thomsen_args()) for L in m.layers])
+    t0 = time.perf_counter()
+    f, s = O.build_cache_3d(cls[:1], N=200, mode_mask=0b010)
+    t1 = time.perf_counter()
+    fs, ss = O.build_cache_3d(cls, N=m.n_dirs // 64, mode_mask=0b001, n_sweep=360)
+    nx, ny, nz = 41, 41, 21
+    sub = np.ascontiguousarray(m.class_id[:nz, :ny, :nx])
+    t2 = time.perf_counter()
+    O.trace_3d(nx, ny, nz, m.h, m.h, m.h, sub, m.radius, fs[0, 0], fs[1, 0], ss[0], 0,
+               N=m.n_dirs // 64)
+    t3 = time.perf_counter()
+    ox, oy, oz, _, _ = O.star_3d(m.radius, m.h, m.h, m.h, m.n_dirs // 64)
+    Es = useful_edges_3d(nx, ny, nz, ox, oy, oz)
+    return {"value": Es * 2 / (t3 - t2), "unit": "useful edge relaxations/s (Dijkstra, tau_R + "
+                                                 "tau_I of one source)",
+            "cores": 1, "kind": "oracle",
+            "sample": "Dijkstra on a 41x41x21 corner (2 fields); cache build of 200 directions "
+                      "of one class and mode",
+            "cache_solves_per_s": 200 / (t1 - t0), "trace_s": t3 - t2,
+            "cpu_count": os.cpu_count()}
 
 
 def cpu_baseline_complex(m, rows, sub, nodes):
