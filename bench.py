@@ -675,7 +675,13 @@ def run_3d(args):
     b = C.Batch()
     for mode in m.modes:
         b.add(desc, cache, K, grid, mode, m.sources, tau_r=outs[mode][0], tau_i=outs[mode][1])
-    tws = torch.empty(C.chert_trace_batch_workspace_bytes(b, opts), dtype=torch.uint8, device=dev)
+    tws = torch.empty(C.chert_trace_autotune_workspace_bytes(b, opts), dtype=torch.uint8,
+                      device=dev)
+    C.chert_build_cache(desc, cls, K, cache, cws, stream=stream)
+    t0 = time.perf_counter()
+    probe_ms = C.chert_trace_autotune(b, opts, tws, stream=stream)
+    tune = {"s": time.perf_counter() - t0, "probe_ms": probe_ms,
+            "bucket_width": opts.bucket_width}
     ox, oy, oz, _, _ = C.chert_star_3d(m.radius, m.h, m.h, m.h, m.n_dirs)
     E = useful_edges_3d(m.nx, m.ny, m.nz, ox, oy, oz)
     times = {"build": [], "trace": []}
@@ -705,7 +711,7 @@ def run_3d(args):
            "trace_s": tt, "useful_edges_per_field": E,
            "useful_edge_relaxations_per_s": E * fields / tt,
            "raw_over_useful": stats.edge_relaxations[0] / (E * fields),
-           "iterations": stats.rounds[0], "repeats": len(times["trace"]),
+           "iterations": stats.rounds[0], "repeats": len(times["trace"]), "autotune": tune,
            "ms_per_step": 1e3 * (tb + tt)}
     res["value"] = res["useful_edge_relaxations_per_s"]
     res["unit"] = "useful edge relaxations/s (3D trace, 16 fields)"

@@ -248,6 +248,10 @@ typedef struct chert_trace_opts {
   int32_t max_rounds; /* cap on relaxation rounds per phase (0 = default)  */
   int32_t push_group; /* star offsets per push work item: 1, 2 or 4 (0 = 2) */
   int32_t launch;     /* CHERT_LAUNCH_PER_ROUND (0) or _PERSISTENT (1)      */
+  double bucket_width;/* 3D frontier: near/far bucket width in units of the
+                         batch's smallest positive edge weight of the field;
+                         0 = one bucket (every improvement is relaxed next
+                         iteration).  Ignored in 2D.  Must be >= 0.        */
   chert_trace_stats *stats_host; /* nullable: filled when the call returns */
 } chert_trace_opts;
 
@@ -305,12 +309,14 @@ int chert_trace_batch(const chert_trace_job *jobs, int32_t n_jobs,
 
 /* Autotuner of the relaxation's launch parameters for a given batch.  The
  * fixed point does not depend on them (every candidate gives the same
- * fields); only the time does.  Candidates: tile shapes 32x32, 64x16,
+ * fields); only the time does.  2D candidates: tile shapes 32x32, 64x16,
  * 16x64, 32x16, 16x32, 128x8; push groups 1, 2, 4; per-round and persistent
- * launch.  Each is timed (HIP events, second of two runs) on a probe batch
- * made of the first source of every job; the fastest is written into
- * o->tile_x, tile_z, push_group and launch (other fields are kept) and its
- * probe time into *best_ms (nullable).  The probe writes the first source's
+ * launch.  3D candidates: frontier bucket widths 0 (one bucket), 4, 16, 32,
+ * 64, 128, 256 (units of the smallest edge weight).  Each is timed (HIP events,
+ * second of two runs) on a probe batch made of the first source of every
+ * job; the fastest is written into o->tile_x, tile_z, push_group, launch and
+ * bucket_width (other fields are kept) and its probe time into *best_ms
+ * (nullable).  The probe writes the first source's
  * rows of the jobs' outputs.  The workspace must hold
  * chert_trace_autotune_workspace_bytes (which also covers the full batch
  * under any candidate).  Synchronous. */

@@ -115,7 +115,7 @@ class TraceOpts(ctypes.Structure):
     _fields_ = [("outputs", ctypes.c_uint32), ("tile_x", ctypes.c_int32),
                 ("tile_z", ctypes.c_int32), ("max_rounds", ctypes.c_int32),
                 ("push_group", ctypes.c_int32), ("launch", ctypes.c_int32),
-                ("stats_host", ctypes.c_void_p)]
+                ("bucket_width", ctypes.c_double), ("stats_host", ctypes.c_void_p)]
 
 
 class SurrogateLayout(ctypes.Structure):
@@ -333,10 +333,11 @@ def make_grid(nx, nz, hx, hz, radius, class_id_dev):
 
 
 def trace_opts(outputs=OUT_ALL, tile_x=0, tile_z=0, max_rounds=0, stats=None, push_group=0,
-               launch=0):
+               launch=0, bucket_width=0.0):
     """stats: a TraceStats to fill (kept referenced by the returned options);
-    launch: LAUNCH_PER_ROUND or LAUNCH_PERSISTENT."""
-    o = TraceOpts(outputs, tile_x, tile_z, max_rounds, push_group, launch,
+    launch: LAUNCH_PER_ROUND or LAUNCH_PERSISTENT; bucket_width: 3D
+    near/far frontier bucket width (units of the smallest edge weight)."""
+    o = TraceOpts(outputs, tile_x, tile_z, max_rounds, push_group, launch, float(bucket_width),
                   ctypes.addressof(stats) if stats is not None else None)
     o._stats = stats
     return o

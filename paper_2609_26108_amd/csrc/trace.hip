@@ -915,9 +915,12 @@ struct PersistArgs {
 // coherent with each other for plain accesses).
 __device__ __forceinline__ bool grid_barrier(const PersistArgs& p) {
   __shared__ int s_ok;
-  __threadfence();
+  // every wave's stores have left it; then one agent-scope release (an L2
+  // write-back of this XCD, which covers every wave of the workgroup)
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
+    __threadfence();
     int ok = 1;
     const uint32_t gen =
         __hip_atomic_load(&p.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -939,9 +942,9 @@ __device__ __forceinline__ bool grid_barrier(const PersistArgs& p) {
     }
     if (!ok) __hip_atomic_store(&p.bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     s_ok = ok;
+    __threadfence();  // acquire: invalidates this CU's L1 and this XCD's L2
   }
   __syncthreads();
-  __threadfence();
   return s_ok != 0;
 }
 
@@ -1521,7 +1524,8 @@ struct Job3 {
 
 struct Prob3 {
   double* tau;
-  int32_t* stamp;
+  int32_t* stamp;   // near-frontier stamps (iteration numbers)
+  int32_t* fstamp;  // far-pile stamps (epoch numbers)
   int job, field;
   int64_t src;
 };
@@ -1538,6 +1542,14 @@ struct R3 {
   int32_t* counts;  // [max_iter + 2] frontier size of each iteration
   int32_t* err;
   unsigned long long* stats;  // [0] iterations run with work, [1] edges examined
+  // near/far buckets: an improvement at or above the problem's threshold
+  // waits in the far pile until the near frontier is empty
+  double* thr;        // [n_prob] current threshold (+inf: one bucket)
+  double* thr_min;    // [n_prob] far-pile minimum (scratch of the split)
+  double* wmin;       // [2] smallest positive edge weight per field
+  double bucket;      // bucket width in units of wmin (0: one bucket)
+  int64_t* far;       // [2][cap] far piles by epoch parity
+  int32_t* far_count; // [2]
 };
 
 constexpr int kFrontierThreads = 256;
@@ -1561,6 +1573,7 @@ __global__ void k_clear3(int32_t* counts, int n_counts, int32_t* err,
   if (blockIdx.x == 0 && threadIdx.x < 4) {
     if (threadIdx.x == 0) *err = 0;
     stats[threadIdx.x] = 0ull;
+    reinterpret_cast<int32_t*>(stats + 8)[threadIdx.x] = 0;  // far-pile counts
   }
 }
 
@@ -1574,12 +1587,80 @@ __global__ void k_init3(R3 a) {
        j += (int64_t)gridDim.x * blockDim.x) {
     P.tau[j] = (j == P.src) ? 0.0 : INFINITY;
     P.stamp[j] = 0;
+    P.fstamp[j] = 0;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0)
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.lists[atomicAdd(&a.counts[0], 1)] = ((int64_t)p << 32) | (int64_t)P.src;
+    const double w = a.wmin[P.field];
+    a.thr[p] = (a.bucket > 0.0 && w < INFINITY) ? a.bucket * w : INFINITY;
+    a.thr_min[p] = INFINITY;
+  }
 }
 
-__global__ void __launch_bounds__(kFrontierThreads) k_relax3(R3 a, int it) {
+// smallest positive finite weight of each field over a job's table
+__global__ void k_wmin3(const double* W, int64_t per_field, double* wmin) {
+  const int f = blockIdx.y;
+  double m = INFINITY;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < per_field;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const double w = W[f * per_field + t];
+    if (w > 0.0 && w < m) m = w;
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off));
+  if (__lane_id() == 0 && m < INFINITY) atomicMin((unsigned long long*)&wmin[f], dbits(m));
+}
+
+__global__ void k_wmin_init3(double* wmin) {
+  if (threadIdx.x < 2) wmin[threadIdx.x] = INFINITY;
+}
+
+// split, step 1: smallest traveltime of each problem's far pile
+__global__ void k_far_min3(R3 a, int epoch) {
+  const int nf = a.far_count[epoch & 1];
+  const int64_t* fl = a.far + (int64_t)(epoch & 1) * a.cap;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nf; q += gridDim.x * blockDim.x) {
+    const int64_t item = fl[q];
+    const int p = (int)(item >> 32);
+    const double t = a.probs[p].tau[item & 0xffffffffLL];
+    atomicMin((unsigned long long*)&a.thr_min[p], dbits(t));
+  }
+}
+
+// split, step 2: thresholds move to the far minimum plus one bucket
+__global__ void k_far_thr3(R3 a, int epoch) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < a.n_prob; p += gridDim.x * blockDim.x) {
+    const double m = a.thr_min[p];
+    if (m < INFINITY) a.thr[p] = m + a.bucket * a.wmin[a.probs[p].field];
+    a.thr_min[p] = INFINITY;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.far_count[(epoch + 1) & 1] = 0;
+}
+
+// split, step 3: far items under the new threshold form iteration it's
+// frontier; the rest move to the next epoch's pile
+__global__ void k_far_split3(R3 a, int epoch, int it) {
+  const int nf = a.far_count[epoch & 1];
+  const int64_t* fl = a.far + (int64_t)(epoch & 1) * a.cap;
+  int64_t* fo = a.far + (int64_t)((epoch + 1) & 1) * a.cap;
+  int64_t* lout = a.lists + (int64_t)(it & 1) * a.cap;
+  for (int base = blockIdx.x * blockDim.x; base < nf; base += gridDim.x * blockDim.x) {
+    const int q = base + threadIdx.x;
+    bool near = false, far = false;
+    int64_t item = 0;
+    if (q < nf) {
+      item = fl[q];
+      const int p = (int)(item >> 32);
+      const int64_t j = item & 0xffffffffLL;
+      const Prob3 P = a.probs[p];
+      if (P.tau[j] < a.thr[p]) near = atomicExch(&P.stamp[j], it) != it;
+      else far = atomicExch(&P.fstamp[j], epoch + 2) != epoch + 2;
+    }
+    append64(near, item, lout, &a.counts[it]);
+    append64(far, item, fo, &a.far_count[(epoch + 1) & 1]);
+  }
+}
+
+__global__ void __launch_bounds__(kFrontierThreads) k_relax3(R3 a, int it, int epoch) {
   const int n_near = a.counts[it];
   if (n_near == 0) return;
   const int64_t total = (int64_t)n_near * a.n_off;
@@ -1589,7 +1670,7 @@ __global__ void __launch_bounds__(kFrontierThreads) k_relax3(R3 a, int it) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
     const int64_t t = base + threadIdx.x;
-    bool want = false;
+    bool want = false, later = false;
     int64_t out = 0;
     if (t < total) {
       ++raw;
@@ -1613,15 +1694,17 @@ __global__ void __launch_bounds__(kFrontierThreads) k_relax3(R3 a, int it) {
           if (cand < P.tau[j]) {
             const unsigned long long old =
                 atomicMin((unsigned long long*)&P.tau[j], dbits(cand));
-            if (dbits(cand) < old && atomicExch(&P.stamp[j], it + 1) != it + 1) {
-              want = true;
+            if (dbits(cand) < old) {
               out = ((int64_t)p << 32) | (int64_t)j;
+              if (cand < a.thr[p]) want = atomicExch(&P.stamp[j], it + 1) != it + 1;
+              else later = atomicExch(&P.fstamp[j], epoch + 1) != epoch + 1;
             }
           }
         }
       }
     }
     append64(want, out, lout, &a.counts[it + 1]);
+    append64(later, out, a.far + (int64_t)(epoch & 1) * a.cap, &a.far_count[epoch & 1]);
   }
   for (int off = 32; off > 0; off >>= 1) raw += __shfl_xor(raw, off);
   if (__lane_id() == 0 && raw) atomicAdd(&a.stats[1], (unsigned long long)raw);
@@ -1632,8 +1715,8 @@ struct Plan3 {
   int R = 0, n_off = 0, n_prob = 0, max_iter = 0;
   int64_t cap = 0;
   size_t off_star = 0, off_lcol = 0, off_jobs = 0, off_probs = 0, off_counts = 0, off_err = 0,
-         off_lists = 0, total = 0;
-  std::vector<size_t> off_W, off_stamp;  // per job, per problem
+         off_lists = 0, off_far = 0, off_thr = 0, total = 0;
+  std::vector<size_t> off_W, off_stamp;  // per job, per problem (near and far stamps)
 };
 
 static int validate_job3(const chert_trace_job& j, uint32_t outs) {
@@ -1673,6 +1756,8 @@ static int make_plan3(const chert_trace_job* jobs, int n_jobs, const chert_trace
   const uint32_t outs = o->outputs;
   if (outs == 0 || !(outs & (CHERT_OUT_TAU_R | CHERT_OUT_TAU_I)))
     return fail(CHERT_ERR_INVALID_ARG, "bad output mask");
+  if (!(o->bucket_width >= 0.0) || !isfinite(o->bucket_width))
+    return fail(CHERT_ERR_INVALID_ARG, "bucket_width must be finite and >= 0");
   for (int j = 0; j < n_jobs; ++j) {
     int rc = validate_job3(jobs[j], outs);
     if (rc) return rc;
@@ -1719,11 +1804,15 @@ static int make_plan3(const chert_trace_job* jobs, int n_jobs, const chert_trace
     const chert_grid* g = jobs[j].g;
     for (int q = 0; q < per * jobs[j].n_src; ++q) {
       P->off_stamp.push_back(off);
-      off += align256((size_t)(g->nx * g->ny * g->nz) * sizeof(int32_t));
+      off += 2 * align256((size_t)(g->nx * g->ny * g->nz) * sizeof(int32_t));
     }
   }
   P->off_lists = off;
   off += align256((size_t)2 * P->cap * sizeof(int64_t));
+  P->off_far = off;
+  off += (o->bucket_width > 0.0) ? align256((size_t)2 * P->cap * sizeof(int64_t)) : 0;
+  P->off_thr = off;
+  off += align256((size_t)2 * P->n_prob * sizeof(double) + 4 * sizeof(double));
   P->total = off;
   return CHERT_OK;
 }
@@ -1765,6 +1854,8 @@ static int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_t
         Prob3 q{};
         q.tau = (field ? J.tau_i_dev : J.tau_r_dev) + (int64_t)i * n;
         q.stamp = (int32_t*)(ws + P.off_stamp[pd.size()]);
+        q.fstamp = (int32_t*)(ws + P.off_stamp[pd.size()] +
+                              align256((size_t)n * sizeof(int32_t)));
         q.job = j;
         q.field = field;
         q.src = J.src_nodes_host[i];
@@ -1818,8 +1909,23 @@ static int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_t
   a.counts = (int32_t*)(ws + P.off_counts);
   a.err = (int32_t*)(ws + P.off_err);
   a.stats = (unsigned long long*)(ws + P.off_err + 64);
+  a.far_count = (int32_t*)(ws + P.off_err + 128);
+  a.thr = (double*)(ws + P.off_thr);
+  a.thr_min = a.thr + P.n_prob;
+  a.wmin = a.thr_min + P.n_prob;
+  a.bucket = o->bucket_width;
+  a.far = o->bucket_width > 0.0 ? (int64_t*)(ws + P.off_far) : nullptr;
   CHERT_LAUNCH("k_clear3", k_clear3, dim3(64), dim3(256), 0, s, a.counts, P.max_iter + 2, a.err,
                a.stats);
+  CHERT_LAUNCH("k_wmin_init3", k_wmin_init3, dim3(1), dim3(64), 0, s, a.wmin);
+  if (a.far) {
+    for (int j = 0; j < n_jobs; ++j) {
+      const int64_t per_field = jobs[j].n_classes * jobs[j].n_classes * (int64_t)P.n_off;
+      int64_t blocks = (per_field + 255) / 256;
+      CHERT_LAUNCH("k_wmin3", k_wmin3, dim3((unsigned)(blocks > 1024 ? 1024 : blocks), 2),
+                   dim3(256), 0, s, (const double*)(ws + P.off_W[j]), per_field, a.wmin);
+    }
+  }
   int64_t max_nodes = 0;
   for (int j = 0; j < n_jobs; ++j) {
     const int64_t n = jobs[j].g->nx * jobs[j].g->ny * jobs[j].g->nz;
@@ -1827,20 +1933,42 @@ static int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_t
   }
   const unsigned gx = (unsigned)((max_nodes + 255) / 256 > 1024 ? 1024 : (max_nodes + 255) / 256);
   CHERT_LAUNCH("k_init3", k_init3, dim3(gx, (unsigned)a.n_prob), dim3(256), 0, s, a);
-  // iterations in groups of 8 between host checks of the frontier sizes
+  // iterations in groups of 8 between host checks of the frontier sizes;
+  // an empty near frontier with a non-empty far pile starts the next bucket
   const int group = 8;
-  int iters = -1;
-  int32_t counts[group];
-  for (int it = 0; it < P.max_iter && iters < 0; it += group) {
+  int iters = -1, epoch = 0;
+  int32_t counts[group + 2];
+  for (int it = 0; it < P.max_iter && iters < 0;) {
     const int nb = it + group > P.max_iter ? P.max_iter - it : group;
     for (int q = 0; q < nb; ++q)
       CHERT_LAUNCH("k_relax3", k_relax3, dim3(kFrontierBlocks), dim3(kFrontierThreads), 0, s, a,
-                   it + q);
+                   it + q, epoch);
     e = hipMemcpyAsync(counts, a.counts + it + 1, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && a.far)
+      e = hipMemcpyAsync(counts + group, a.far_count + (epoch & 1), sizeof(int32_t),
+                         hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
-    for (int q = 0; q < nb && iters < 0; ++q)
-      if (counts[q] == 0) iters = it + q + 1;
+    int empty = -1;
+    for (int q = 0; q < nb && empty < 0; ++q)
+      if (counts[q] == 0) empty = it + q + 1;
+    if (empty < 0) {
+      it += nb;
+      continue;
+    }
+    if (!a.far || counts[group] == 0) {
+      iters = empty;
+      break;
+    }
+    // next bucket: its frontier becomes iteration `empty`'s input
+    const int nfar = counts[group];
+    const unsigned fb = (unsigned)((nfar + 255) / 256 > 4096 ? 4096 : (nfar + 255) / 256);
+    CHERT_LAUNCH("k_far_min3", k_far_min3, dim3(fb), dim3(256), 0, s, a, epoch);
+    CHERT_LAUNCH("k_far_thr3", k_far_thr3, dim3((a.n_prob + 255) / 256), dim3(256), 0, s, a,
+                 epoch);
+    CHERT_LAUNCH("k_far_split3", k_far_split3, dim3(fb), dim3(256), 0, s, a, epoch, empty);
+    ++epoch;
+    it = empty;
   }
   int32_t herr = 0;
   unsigned long long hstats[2] = {0, 0};
@@ -1948,10 +2076,17 @@ const int kTuneGroups[] = {1, 2, 4};
 const int kTuneLaunch[] = {CHERT_LAUNCH_PER_ROUND, CHERT_LAUNCH_PERSISTENT};
 }  // namespace
 
+const double kTuneBuckets[] = {0.0, 4.0, 16.0, 32.0, 64.0, 128.0, 256.0};
+
 extern "C" size_t chert_trace_autotune_workspace_bytes(const chert_trace_job* jobs,
                                                        int32_t n_jobs,
                                                        const chert_trace_opts* o) {
   if (!o) return 0;
+  if (is_3d_batch(jobs, n_jobs)) {  // the bucketed plan is the largest
+    chert_trace_opts c = *o;
+    c.bucket_width = 1.0;
+    return chert_trace_batch_workspace_bytes(jobs, n_jobs, &c);
+  }
   size_t best = 0;
   for (const auto& t : kTuneTiles) {
     chert_trace_opts c = *o;
@@ -1977,7 +2112,30 @@ extern "C" int chert_trace_autotune(const chert_trace_job* jobs, int32_t n_jobs,
   double best = -1.0;
   chert_trace_opts pick = *o;
   int tried = 0;
-  for (const auto& t : kTuneTiles)
+  if (is_3d_batch(jobs, n_jobs)) {
+    for (double bw : kTuneBuckets) {
+      chert_trace_opts c = *o;
+      c.bucket_width = bw;
+      c.stats_host = nullptr;
+      int rc = CHERT_OK;
+      float ms = 0.f;
+      for (int rep = 0; rep < 2 && rc == CHERT_OK; ++rep) {
+        (void)hipEventRecord(e0, s);
+        rc = trace_batch(probe.data(), n_jobs, &c, workspace_dev, workspace_bytes, s);
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) rc = CHERT_ERR_HIP;
+        if (rc == CHERT_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+      }
+      if (rc != CHERT_OK) continue;
+      ++tried;
+      if (best < 0.0 || ms < best) {
+        best = ms;
+        pick = c;
+      }
+    }
+  }
+  for (const auto& t : kTuneTiles) {
+    if (is_3d_batch(jobs, n_jobs)) break;
     for (int G : kTuneGroups)
       for (int L : kTuneLaunch) {
         chert_trace_opts c = *o;
@@ -2004,6 +2162,7 @@ extern "C" int chert_trace_autotune(const chert_trace_job* jobs, int32_t n_jobs,
           pick = c;
         }
       }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (tried == 0) return fail(CHERT_ERR_INVALID_ARG, "no candidate fits the workspace");
@@ -2011,6 +2170,7 @@ extern "C" int chert_trace_autotune(const chert_trace_job* jobs, int32_t n_jobs,
   o->tile_z = pick.tile_z;
   o->push_group = pick.push_group;
   o->launch = pick.launch;
+  o->bucket_width = pick.bucket_width;
   if (best_ms) *best_ms = best;
   return CHERT_OK;
 }

@@ -97,12 +97,12 @@ def small3d():
     return m, cls, f, s
 
 
-def trace3(G, m, cache, desc, K, mode):
+def trace3(G, m, cache, desc, K, mode, bucket=0.0):
     Cm = C()
     cid = torch.from_numpy(np.ascontiguousarray(m.class_id.reshape(-1), dtype=np.int32)).to(G.DEV)
     g = Cm.make_grid3(m.nx, m.ny, m.nz, m.h, m.radius, cid)
     stats = Cm.TraceStats()
-    o = Cm.trace_opts(Cm.OUT_TAU_R | Cm.OUT_TAU_I, stats=stats)
+    o = Cm.trace_opts(Cm.OUT_TAU_R | Cm.OUT_TAU_I, stats=stats, bucket_width=bucket)
     S, n = len(m.sources), m.n_nodes
     tr = torch.empty((S, n), dtype=torch.float64, device=G.DEV)
     ti = torch.empty((S, n), dtype=torch.float64, device=G.DEV)
@@ -113,16 +113,18 @@ def trace3(G, m, cache, desc, K, mode):
     return tr.cpu().numpy(), ti.cpu().numpy(), stats.as_dict()
 
 
-def test_trace_3d_imported_cache_bitwise(G, small3d):
+@pytest.mark.parametrize("bucket", [0.0, 3.0, 16.0])
+def test_trace_3d_imported_cache_bitwise(G, small3d, bucket):
     """On the oracle's cache, every 3D traveltime (three sources, two modes,
-    tau_R and tau_I) equals the oracle's Dijkstra bitwise."""
+    tau_R and tau_I) equals the oracle's Dijkstra bitwise, with one frontier
+    bucket or near/far buckets of several widths."""
     Cm = C()
     m, cls, f, s = small3d
     K = cls.shape[0]
     desc = Cm.cache_desc(dim=3, n_dirs=400, modes=(0, 1), n_sweep=360)
     cache = G.import_cache(f, s, desc, K)
     for mode in (0, 1):
-        tr, ti, st = trace3(G, m, cache, desc, K, mode)
+        tr, ti, st = trace3(G, m, cache, desc, K, mode, bucket)
         print("mode", mode, st)
         for si, src in enumerate(m.sources):
             o = O.trace_3d(m.nx, m.ny, m.nz, m.h, m.h, m.h, m.class_id, m.radius, f[0, mode],
@@ -162,3 +164,31 @@ def test_trace_3d_invalid_class_id_reported(G, small3d):
     with pytest.raises(Cm.ChertError) as e:
         trace3(G, m2, cache, desc, K, 0)
     assert e.value.code == 1
+
+
+def test_trace_3d_autotuned_bucket(G, small3d):
+    """The autotuner picks a bucket width for a 3D batch; the batch traced
+    with it is still bitwise the oracle's."""
+    Cm = C()
+    m, cls, f, s = small3d
+    K = cls.shape[0]
+    desc = Cm.cache_desc(dim=3, n_dirs=400, modes=(0, 1), n_sweep=360)
+    cache = G.import_cache(f, s, desc, K)
+    cid = torch.from_numpy(np.ascontiguousarray(m.class_id.reshape(-1), dtype=np.int32)).to(G.DEV)
+    g = Cm.make_grid3(m.nx, m.ny, m.nz, m.h, m.radius, cid)
+    S, n = len(m.sources), m.n_nodes
+    tr = torch.empty((S, n), dtype=torch.float64, device=G.DEV)
+    b = Cm.Batch().add(desc, cache, K, g, 1, m.sources, tau_r=tr)
+    o = Cm.trace_opts(Cm.OUT_TAU_R)
+    ws = torch.empty(Cm.chert_trace_autotune_workspace_bytes(b, o), dtype=torch.uint8,
+                     device=G.DEV)
+    ms = Cm.chert_trace_autotune(b, o, ws)
+    print("3D autotuned bucket", o.bucket_width, ms)
+    assert o.bucket_width in (0.0, 4.0, 16.0, 32.0, 64.0, 128.0, 256.0)
+    tr.fill_(-1.0)
+    Cm.chert_trace_batch(b, o, ws)
+    torch.cuda.synchronize()
+    for si, src in enumerate(m.sources):
+        ref = O.trace_3d(m.nx, m.ny, m.nz, m.h, m.h, m.h, m.class_id, m.radius, f[0, 1], f[1, 1],
+                         s[1], src, N=400)
+        assert np.array_equal(tr[si].cpu().numpy(), ref["tauR"])
