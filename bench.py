@@ -38,12 +38,12 @@ FP64_VALU_PEAK_TOPS = 39.3  # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz, one o
 # Valid only for the kernel source it was measured on.
 MEASURED_TRAFFIC = {
     "source": "paper_2609_26108_amd/csrc/trace.hip",
-    "source_sha256_16": "ed2cbc29a0e6d6f1",
+    "source_sha256_16": "92eb424bf739df69",
     "fetch_scale": 2.0, "write_scale": 1.0,
     "kib_per_dispatch": {  # kernel -> (FETCH_SIZE KiB, WRITE_SIZE KiB)
-        "k_relax_tau": (2417.1, 728.0),
-        "k_relax_hop": (3030.8, 230.2),
-        "k_relax_tstar": (1557.4, 172.6),
+        "k_relax_tau": (2424.3, 731.3),
+        "k_relax_hop": (3036.7, 233.1),
+        "k_relax_tstar": (1564.3, 173.9),
     },
 }
 

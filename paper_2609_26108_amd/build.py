@@ -25,6 +25,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 SOURCES = [
     ("cache_build.hip", ["-ffp-contract=fast"]),
     ("trace.hip", ["-ffp-contract=off"]),
+    ("trace3d.hip", ["-ffp-contract=off"]),
     ("surrogate.hip", ["-ffp-contract=fast"]),
     ("abi_host.cpp", ["-ffp-contract=off", "-x", "hip"]),
 ]

@@ -35,6 +35,14 @@ void fibonacci(int N, double* f);
 int star_3d(int R, double hx, double hy, double hz, int N, int32_t* ox, int32_t* oy, int32_t* oz,
             double* L, int32_t* bin);
 
+// 3D batches (trace3d.hip): all jobs on 3D grids
+inline bool is_3d_batch(const chert_trace_job* jobs, int n_jobs) {
+  return jobs && n_jobs > 0 && jobs[0].g && jobs[0].g->dim == 3;
+}
+int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o,
+                   void* workspace_dev, size_t workspace_bytes, hipStream_t s);
+size_t trace_batch_3d_bytes(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o);
+
 // Kernel timing for chert_prof_*: returns a slot (or -1 when profiling is
 // off) after recording a start event on the stream; prof_end records the stop.
 int prof_begin(const char* name, hipStream_t s);

@@ -1,0 +1,548 @@
+// 3D traveltimes (eq 31 on a 3D forward star) for gfx950: a node-frontier
+// label-correcting iteration with near/far buckets.  See trace.hip for the
+// 2D tile relaxation; both reach the same fixed point as Dijkstra.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "chert.h"
+#include "chert_internal.h"
+
+namespace chert {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+__device__ __forceinline__ unsigned long long dbits(double x) {
+  return (unsigned long long)__double_as_longlong(x);
+}
+
+constexpr int kFieldR = 0;
+
+// W[f][ki][kj][o] (eqs 28-30 in this operation order, no contraction) from a
+// mode's slice of a 3D cache: the column of offset o is its Fibonacci bin
+__global__ void k_weights3(double* W, int K, int n_off, const double* V, const double* A,
+                           const int32_t* st, int n_cols, const double* L, const int32_t* col) {
+  const int64_t total = 2LL * K * K * n_off;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int o = (int)(t % n_off);
+    int64_t r = t / n_off;
+    const int kj = (int)(r % K);
+    r /= K;
+    const int ki = (int)(r % K);
+    const int f = (int)(r / K);
+    const int b = col[o];
+    const int bad = CHERT_ST_NO_BRACKET | CHERT_ST_FLUID | CHERT_ST_NONPHYS;
+    const int64_t ei = (int64_t)ki * n_cols + b, ej = (int64_t)kj * n_cols + b;
+    double w;
+    if ((st[ei] & bad) || (st[ej] & bad)) w = INFINITY;
+    else if (f == kFieldR) w = __ddiv_rn(L[o], __dmul_rn(0.5, __dadd_rn(V[ei], V[ej])));
+    else w = __dmul_rn(L[o], __dmul_rn(0.5, __dadd_rn(A[ei], A[ej])));
+    W[t] = w;
+  }
+}
+
+// Node-frontier label-correcting relaxation on 3D grids (eq 31 over the 3D
+// forward star, edge costs of eqs 27-30 from a Fibonacci-direction cache).
+// Iteration it relaxes every out-edge of the (problem, node) items whose
+// traveltime dropped in iteration it - 1: an improved head is claimed with a
+// 64-bit atomicMin on the bits of the (non-negative) double, stamped so that
+// it enters the next frontier once, and appended with one atomic per
+// wavefront (ballot + prefix count).  The fixed point is the same minimum
+// over path folds as the 2D tiles and Dijkstra reach.
+
+struct Job3 {
+  int nx, ny, nz, K;
+  const int32_t* cls;
+  const double* W;  // [2][K][K][n_off]
+};
+
+struct Prob3 {
+  double* tau;
+  int32_t* stamp;   // near-frontier stamps (iteration numbers)
+  int32_t* fstamp;  // far-pile stamps (epoch numbers)
+  int job, field;
+  int64_t src;
+};
+
+struct R3 {
+  const Job3* jobs;
+  const Prob3* probs;
+  int n_prob, n_off;
+  const int32_t* ox;
+  const int32_t* oy;
+  const int32_t* oz;
+  int64_t* lists;   // [2][cap] items (problem << 32 | node), by iteration parity
+  int64_t cap;
+  int32_t* counts;  // [max_iter + 2] frontier size of each iteration
+  int32_t* err;
+  unsigned long long* stats;  // [0] iterations run with work, [1] edges examined
+  // near/far buckets: an improvement at or above the problem's threshold
+  // waits in the far pile until the near frontier is empty
+  double* thr;        // [n_prob] current threshold (+inf: one bucket)
+  double* thr_min;    // [n_prob] far-pile minimum (scratch of the split)
+  double* wmin;       // [2] smallest positive edge weight per field
+  double bucket;      // bucket width in units of wmin (0: one bucket)
+  int64_t* far;       // [2][cap] far piles by epoch parity
+  int32_t* far_count; // [2]
+};
+
+constexpr int kFrontierThreads = 256;
+constexpr int kFrontierBlocks = 4096;
+
+__device__ __forceinline__ void append64(bool flag, int64_t item, int64_t* list, int32_t* count) {
+  const unsigned long long b = __ballot(flag);
+  if (b == 0ull) return;
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)b) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(count, __popcll(b));
+  base = __shfl(base, leader);
+  if (flag) list[base + __popcll(b & ((1ull << lane) - 1ull))] = item;
+}
+
+__global__ void k_clear3(int32_t* counts, int n_counts, int32_t* err,
+                         unsigned long long* stats) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n_counts; t += gridDim.x * blockDim.x)
+    counts[t] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < 4) {
+    if (threadIdx.x == 0) *err = 0;
+    stats[threadIdx.x] = 0ull;
+    reinterpret_cast<int32_t*>(stats + 8)[threadIdx.x] = 0;  // far-pile counts
+  }
+}
+
+// blockIdx.y = problem: tau = inf (0 at the source), stamps 0, source queued
+__global__ void k_init3(R3 a) {
+  const int p = blockIdx.y;
+  const Prob3 P = a.probs[p];
+  const Job3 J = a.jobs[P.job];
+  const int64_t n = (int64_t)J.nx * J.ny * J.nz;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    P.tau[j] = (j == P.src) ? 0.0 : INFINITY;
+    P.stamp[j] = 0;
+    P.fstamp[j] = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.lists[atomicAdd(&a.counts[0], 1)] = ((int64_t)p << 32) | (int64_t)P.src;
+    const double w = a.wmin[P.field];
+    a.thr[p] = (a.bucket > 0.0 && w < INFINITY) ? a.bucket * w : INFINITY;
+    a.thr_min[p] = INFINITY;
+  }
+}
+
+// smallest positive finite weight of each field over a job's table
+__global__ void k_wmin3(const double* W, int64_t per_field, double* wmin) {
+  const int f = blockIdx.y;
+  double m = INFINITY;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < per_field;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const double w = W[f * per_field + t];
+    if (w > 0.0 && w < m) m = w;
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off));
+  if (__lane_id() == 0 && m < INFINITY) atomicMin((unsigned long long*)&wmin[f], dbits(m));
+}
+
+__global__ void k_wmin_init3(double* wmin) {
+  if (threadIdx.x < 2) wmin[threadIdx.x] = INFINITY;
+}
+
+// split, step 1: smallest traveltime of each problem's far pile; per-block
+// minima in LDS (few problems, many items: one global atomic per problem
+// and block instead of one per item)
+constexpr int kFarMinLds = 2048;
+__global__ void __launch_bounds__(256) k_far_min3(R3 a, int epoch) {
+  __shared__ unsigned long long s_min[kFarMinLds];
+  const bool lds = a.n_prob <= kFarMinLds;
+  if (lds)
+    for (int p = threadIdx.x; p < a.n_prob; p += blockDim.x) s_min[p] = dbits(INFINITY);
+  __syncthreads();
+  const int nf = a.far_count[epoch & 1];
+  const int64_t* fl = a.far + (int64_t)(epoch & 1) * a.cap;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nf; q += gridDim.x * blockDim.x) {
+    const int64_t item = fl[q];
+    const int p = (int)(item >> 32);
+    const double t = a.probs[p].tau[item & 0xffffffffLL];
+    if (lds) atomicMin(&s_min[p], dbits(t));
+    else atomicMin((unsigned long long*)&a.thr_min[p], dbits(t));
+  }
+  __syncthreads();
+  if (lds)
+    for (int p = threadIdx.x; p < a.n_prob; p += blockDim.x)
+      if (s_min[p] != dbits(INFINITY)) atomicMin((unsigned long long*)&a.thr_min[p], s_min[p]);
+}
+
+// split, step 2: thresholds move to the far minimum plus one bucket
+__global__ void k_far_thr3(R3 a, int epoch) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < a.n_prob; p += gridDim.x * blockDim.x) {
+    const double m = a.thr_min[p];
+    if (m < INFINITY) a.thr[p] = m + a.bucket * a.wmin[a.probs[p].field];
+    a.thr_min[p] = INFINITY;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.far_count[(epoch + 1) & 1] = 0;
+}
+
+// split, step 3: far items under the new threshold form iteration it's
+// frontier; the rest move to the next epoch's pile
+__global__ void k_far_split3(R3 a, int epoch, int it) {
+  const int nf = a.far_count[epoch & 1];
+  const int64_t* fl = a.far + (int64_t)(epoch & 1) * a.cap;
+  int64_t* fo = a.far + (int64_t)((epoch + 1) & 1) * a.cap;
+  int64_t* lout = a.lists + (int64_t)(it & 1) * a.cap;
+  for (int base = blockIdx.x * blockDim.x; base < nf; base += gridDim.x * blockDim.x) {
+    const int q = base + threadIdx.x;
+    bool near = false, far = false;
+    int64_t item = 0;
+    if (q < nf) {
+      item = fl[q];
+      const int p = (int)(item >> 32);
+      const int64_t j = item & 0xffffffffLL;
+      const Prob3 P = a.probs[p];
+      if (P.tau[j] < a.thr[p]) near = atomicExch(&P.stamp[j], it) != it;
+      else far = atomicExch(&P.fstamp[j], epoch + 2) != epoch + 2;
+    }
+    append64(near, item, lout, &a.counts[it]);
+    append64(far, item, fo, &a.far_count[(epoch + 1) & 1]);
+  }
+}
+
+__global__ void __launch_bounds__(kFrontierThreads) k_relax3(R3 a, int it, int epoch) {
+  const int n_near = a.counts[it];
+  if (n_near == 0) return;
+  const int64_t total = (int64_t)n_near * a.n_off;
+  const int64_t* lin = a.lists + (int64_t)(it & 1) * a.cap;
+  int64_t* lout = a.lists + (int64_t)((it + 1) & 1) * a.cap;
+  long long raw = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
+    const int64_t t = base + threadIdx.x;
+    bool want = false, later = false;
+    int64_t out = 0;
+    if (t < total) {
+      ++raw;
+      const int64_t f = t / a.n_off;
+      const int o = (int)(t - f * a.n_off);
+      const int64_t item = lin[f];
+      const int p = (int)(item >> 32);
+      const int i = (int)(item & 0xffffffffLL);
+      const Prob3 P = a.probs[p];
+      const Job3 J = a.jobs[P.job];
+      const int x = i % J.nx, r = i / J.nx, y = r % J.ny, z = r / J.ny;
+      const int X = x + a.ox[o], Y = y + a.oy[o], Z = z + a.oz[o];
+      if (X >= 0 && X < J.nx && Y >= 0 && Y < J.ny && Z >= 0 && Z < J.nz) {
+        const int j = X + J.nx * (Y + J.ny * Z);
+        const int ci = J.cls[i], cj = J.cls[j];
+        if (ci < 0 || ci >= J.K || cj < 0 || cj >= J.K) {
+          *a.err = 1;
+        } else {
+          const double w = J.W[(((int64_t)P.field * J.K + ci) * J.K + cj) * a.n_off + o];
+          const double cand = __dadd_rn(P.tau[i], w);
+          if (cand < P.tau[j]) {
+            const unsigned long long old =
+                atomicMin((unsigned long long*)&P.tau[j], dbits(cand));
+            if (dbits(cand) < old) {
+              out = ((int64_t)p << 32) | (int64_t)j;
+              if (cand < a.thr[p]) want = atomicExch(&P.stamp[j], it + 1) != it + 1;
+              else later = atomicExch(&P.fstamp[j], epoch + 1) != epoch + 1;
+            }
+          }
+        }
+      }
+    }
+    append64(want, out, lout, &a.counts[it + 1]);
+    append64(later, out, a.far + (int64_t)(epoch & 1) * a.cap, &a.far_count[epoch & 1]);
+  }
+  for (int off = 32; off > 0; off >>= 1) raw += __shfl_xor(raw, off);
+  if (__lane_id() == 0 && raw) atomicAdd(&a.stats[1], (unsigned long long)raw);
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.stats[0], 1ull);
+}
+
+struct Plan3 {
+  int R = 0, n_off = 0, n_prob = 0, max_iter = 0;
+  int64_t cap = 0;
+  size_t off_star = 0, off_lcol = 0, off_jobs = 0, off_probs = 0, off_counts = 0, off_err = 0,
+         off_lists = 0, off_far = 0, off_thr = 0, total = 0;
+  std::vector<size_t> off_W, off_stamp;  // per job, per problem (near and far stamps)
+};
+
+static int validate_job3(const chert_trace_job& j, uint32_t outs) {
+  chert_cache_layout lay;
+  int rc = chert_cache_layout_of(j.d, j.n_classes, &lay);
+  if (rc) return rc;
+  const chert_grid* g = j.g;
+  if (!g || g->dim != 3) return fail(CHERT_ERR_INVALID_ARG, "a 3D batch needs 3D grids");
+  if (j.d->dim != 3) return fail(CHERT_ERR_INVALID_ARG, "a 3D grid needs a 3D cache");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1 || g->nx * g->ny * g->nz >= 0x7fffffffLL)
+    return fail(CHERT_ERR_INVALID_ARG, "grid size out of range");
+  if (g->radius < 1 || g->radius > kMaxRadius3)
+    return fail(CHERT_ERR_INVALID_ARG, "3D radius must be 1..4");
+  if (!(g->hx > 0.0) || !(g->hy > 0.0) || !(g->hz > 0.0) || !isfinite(g->hx) ||
+      !isfinite(g->hy) || !isfinite(g->hz))
+    return fail(CHERT_ERR_INVALID_ARG, "spacing must be positive");
+  if (!g->class_id_dev) return fail(CHERT_ERR_UNSUPPORTED, "3D grids need a class map");
+  if (outs & ~(uint32_t)(CHERT_OUT_TAU_R | CHERT_OUT_TAU_I))
+    return fail(CHERT_ERR_UNSUPPORTED, "3D traces give tau_R and tau_I");
+  if (j.mode < 0 || j.mode > 2 || !(j.d->mode_mask & (1u << j.mode)))
+    return fail(CHERT_ERR_INVALID_ARG, "mode not in the cache");
+  if (!j.cache_dev) return fail(CHERT_ERR_INVALID_ARG, "null cache");
+  if (j.n_src < 1 || !j.src_nodes_host) return fail(CHERT_ERR_INVALID_ARG, "need sources");
+  const int64_t n = g->nx * g->ny * g->nz;
+  for (int i = 0; i < j.n_src; ++i)
+    if (j.src_nodes_host[i] < 0 || j.src_nodes_host[i] >= n)
+      return fail(CHERT_ERR_INVALID_ARG, "source out of range");
+  if ((outs & CHERT_OUT_TAU_R) && !j.tau_r_dev) return fail(CHERT_ERR_INVALID_ARG, "null tau_r");
+  if ((outs & CHERT_OUT_TAU_I) && !j.tau_i_dev) return fail(CHERT_ERR_INVALID_ARG, "null tau_i");
+  return CHERT_OK;
+}
+
+static int make_plan3(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o,
+                      Plan3* P) {
+  if (!jobs || n_jobs < 1) return fail(CHERT_ERR_INVALID_ARG, "need at least one job");
+  if (!o) return fail(CHERT_ERR_INVALID_ARG, "null options");
+  const uint32_t outs = o->outputs;
+  if (outs == 0 || !(outs & (CHERT_OUT_TAU_R | CHERT_OUT_TAU_I)))
+    return fail(CHERT_ERR_INVALID_ARG, "bad output mask");
+  if (!(o->bucket_width >= 0.0) || !isfinite(o->bucket_width))
+    return fail(CHERT_ERR_INVALID_ARG, "bucket_width must be finite and >= 0");
+  for (int j = 0; j < n_jobs; ++j) {
+    int rc = validate_job3(jobs[j], outs);
+    if (rc) return rc;
+    if (jobs[j].g->radius != jobs[0].g->radius)
+      return fail(CHERT_ERR_INVALID_ARG, "all jobs of a batch need the same radius");
+  }
+  P->R = jobs[0].g->radius;
+  P->n_off = star_3d(P->R, 1.0, 1.0, 1.0, 2, nullptr, nullptr, nullptr, nullptr, nullptr);
+  const int per = ((outs & CHERT_OUT_TAU_R) ? 1 : 0) + ((outs & CHERT_OUT_TAU_I) ? 1 : 0);
+  int64_t span = 0;
+  P->n_prob = 0;
+  P->cap = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    const chert_grid* g = jobs[j].g;
+    const int64_t n = g->nx * g->ny * g->nz;
+    P->n_prob += per * jobs[j].n_src;
+    P->cap += (int64_t)per * jobs[j].n_src * n;
+    const int64_t sp = g->nx + g->ny + g->nz;
+    if (sp > span) span = sp;
+  }
+  if (P->n_prob > 65535 || P->cap >= 0x7fffffffLL)
+    return fail(CHERT_ERR_UNSUPPORTED, "batch too large for one launch");
+  P->max_iter = (o->max_rounds > 0) ? o->max_rounds : 4096 + 64 * (int)span;
+  size_t off = 0;
+  P->off_star = off;
+  off += align256((size_t)3 * kMaxOffsets3 * sizeof(int32_t));
+  P->off_lcol = off;
+  off += align256((size_t)n_jobs * P->n_off * (sizeof(double) + sizeof(int32_t)));
+  P->off_jobs = off;
+  off += align256((size_t)n_jobs * sizeof(Job3));
+  P->off_probs = off;
+  off += align256((size_t)P->n_prob * sizeof(Prob3));
+  P->off_counts = off;
+  off += align256((size_t)(P->max_iter + 2) * sizeof(int32_t));
+  P->off_err = off;
+  off += 256;
+  P->off_W.clear();
+  for (int j = 0; j < n_jobs; ++j) {
+    P->off_W.push_back(off);
+    off += align256((size_t)2 * jobs[j].n_classes * jobs[j].n_classes * P->n_off * sizeof(double));
+  }
+  P->off_stamp.clear();
+  for (int j = 0; j < n_jobs; ++j) {
+    const chert_grid* g = jobs[j].g;
+    for (int q = 0; q < per * jobs[j].n_src; ++q) {
+      P->off_stamp.push_back(off);
+      off += 2 * align256((size_t)(g->nx * g->ny * g->nz) * sizeof(int32_t));
+    }
+  }
+  P->off_lists = off;
+  off += align256((size_t)2 * P->cap * sizeof(int64_t));
+  P->off_far = off;
+  off += (o->bucket_width > 0.0) ? align256((size_t)2 * P->cap * sizeof(int64_t)) : 0;
+  P->off_thr = off;
+  off += align256((size_t)2 * P->n_prob * sizeof(double) + 4 * sizeof(double));
+  P->total = off;
+  return CHERT_OK;
+}
+
+int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o,
+                   void* workspace_dev, size_t workspace_bytes, hipStream_t s) {
+  Plan3 P;
+  int rc = make_plan3(jobs, n_jobs, o, &P);
+  if (rc) return rc;
+  if (!workspace_dev || workspace_bytes < P.total)
+    return fail(CHERT_ERR_INVALID_ARG, "workspace too small");
+  uint8_t* ws = (uint8_t*)workspace_dev;
+  const uint32_t outs = o->outputs;
+  // star (shared) and per-job lengths and cache columns
+  std::vector<int32_t> star((size_t)3 * kMaxOffsets3, 0);
+  std::vector<uint8_t> lcol((size_t)n_jobs * P.n_off * (sizeof(double) + sizeof(int32_t)));
+  double* hL = (double*)lcol.data();
+  int32_t* hcol = (int32_t*)(hL + (size_t)n_jobs * P.n_off);
+  for (int j = 0; j < n_jobs; ++j) {
+    const chert_grid* g = jobs[j].g;
+    star_3d(P.R, g->hx, g->hy, g->hz, jobs[j].d->n_dirs, star.data(), star.data() + kMaxOffsets3,
+            star.data() + 2 * kMaxOffsets3, hL + (size_t)j * P.n_off,
+            hcol + (size_t)j * P.n_off);
+  }
+  std::vector<Job3> jd(n_jobs);
+  std::vector<Prob3> pd;
+  for (int j = 0; j < n_jobs; ++j) {
+    const chert_trace_job& J = jobs[j];
+    jd[j].nx = (int)J.g->nx;
+    jd[j].ny = (int)J.g->ny;
+    jd[j].nz = (int)J.g->nz;
+    jd[j].K = (int)J.n_classes;
+    jd[j].cls = J.g->class_id_dev;
+    jd[j].W = (const double*)(ws + P.off_W[j]);
+    const int64_t n = J.g->nx * J.g->ny * J.g->nz;
+    for (int i = 0; i < J.n_src; ++i) {
+      for (int field = 0; field < 2; ++field) {
+        if (!(outs & (field ? CHERT_OUT_TAU_I : CHERT_OUT_TAU_R))) continue;
+        Prob3 q{};
+        q.tau = (field ? J.tau_i_dev : J.tau_r_dev) + (int64_t)i * n;
+        q.stamp = (int32_t*)(ws + P.off_stamp[pd.size()]);
+        q.fstamp = (int32_t*)(ws + P.off_stamp[pd.size()] +
+                              align256((size_t)n * sizeof(int32_t)));
+        q.job = j;
+        q.field = field;
+        q.src = J.src_nodes_host[i];
+        pd.push_back(q);
+      }
+    }
+  }
+  int32_t* dstar = (int32_t*)(ws + P.off_star);
+  double* dL = (double*)(ws + P.off_lcol);
+  int32_t* dcol = (int32_t*)(dL + (size_t)n_jobs * P.n_off);
+  Job3* djobs = (Job3*)(ws + P.off_jobs);
+  Prob3* dprobs = (Prob3*)(ws + P.off_probs);
+  hipError_t e = hipMemcpyAsync(dstar, star.data(), star.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dL, lcol.data(), lcol.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(djobs, jd.data(), jd.size() * sizeof(Job3), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dprobs, pd.data(), pd.size() * sizeof(Prob3), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // host buffers are locals
+  if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+
+  for (int j = 0; j < n_jobs; ++j) {
+    const chert_trace_job& J = jobs[j];
+    chert_cache_layout lay;
+    chert_cache_layout_of(J.d, J.n_classes, &lay);
+    const uint8_t* cache = (const uint8_t*)J.cache_dev;
+    const int64_t K = J.n_classes;
+    const int n_cols = J.d->n_dirs;
+    const int64_t ent = 3 * K * (int64_t)n_cols;
+    const int64_t mslice = (int64_t)J.mode * K * n_cols;
+    const double* fields = (const double*)(cache + lay.fields_offset);
+    int64_t tw = 2 * K * K * P.n_off;
+    int64_t blocks = (tw + 255) / 256;
+    CHERT_LAUNCH("k_weights3", k_weights3, dim3((unsigned)(blocks > 65536 ? 65536 : blocks)),
+                 dim3(256), 0, s, (double*)(ws + P.off_W[j]), (int)K, P.n_off,
+                 fields + CHERT_F_V * ent + mslice, fields + CHERT_F_A * ent + mslice,
+                 (const int32_t*)(cache + lay.status_offset) + mslice, n_cols,
+                 dL + (size_t)j * P.n_off, dcol + (size_t)j * P.n_off);
+  }
+  R3 a{};
+  a.jobs = djobs;
+  a.probs = dprobs;
+  a.n_prob = (int)pd.size();
+  a.n_off = P.n_off;
+  a.ox = dstar;
+  a.oy = dstar + kMaxOffsets3;
+  a.oz = dstar + 2 * kMaxOffsets3;
+  a.lists = (int64_t*)(ws + P.off_lists);
+  a.cap = P.cap;
+  a.counts = (int32_t*)(ws + P.off_counts);
+  a.err = (int32_t*)(ws + P.off_err);
+  a.stats = (unsigned long long*)(ws + P.off_err + 64);
+  a.far_count = (int32_t*)(ws + P.off_err + 128);
+  a.thr = (double*)(ws + P.off_thr);
+  a.thr_min = a.thr + P.n_prob;
+  a.wmin = a.thr_min + P.n_prob;
+  a.bucket = o->bucket_width;
+  a.far = o->bucket_width > 0.0 ? (int64_t*)(ws + P.off_far) : nullptr;
+  CHERT_LAUNCH("k_clear3", k_clear3, dim3(64), dim3(256), 0, s, a.counts, P.max_iter + 2, a.err,
+               a.stats);
+  CHERT_LAUNCH("k_wmin_init3", k_wmin_init3, dim3(1), dim3(64), 0, s, a.wmin);
+  if (a.far) {
+    for (int j = 0; j < n_jobs; ++j) {
+      const int64_t per_field = jobs[j].n_classes * jobs[j].n_classes * (int64_t)P.n_off;
+      int64_t blocks = (per_field + 255) / 256;
+      CHERT_LAUNCH("k_wmin3", k_wmin3, dim3((unsigned)(blocks > 1024 ? 1024 : blocks), 2),
+                   dim3(256), 0, s, (const double*)(ws + P.off_W[j]), per_field, a.wmin);
+    }
+  }
+  int64_t max_nodes = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    const int64_t n = jobs[j].g->nx * jobs[j].g->ny * jobs[j].g->nz;
+    if (n > max_nodes) max_nodes = n;
+  }
+  const unsigned gx = (unsigned)((max_nodes + 255) / 256 > 1024 ? 1024 : (max_nodes + 255) / 256);
+  CHERT_LAUNCH("k_init3", k_init3, dim3(gx, (unsigned)a.n_prob), dim3(256), 0, s, a);
+  // iterations in groups of 8 between host checks of the frontier sizes;
+  // an empty near frontier with a non-empty far pile starts the next bucket
+  const int group = 8;
+  int iters = -1, epoch = 0;
+  int32_t counts[group + 2];
+  for (int it = 0; it < P.max_iter && iters < 0;) {
+    const int nb = it + group > P.max_iter ? P.max_iter - it : group;
+    for (int q = 0; q < nb; ++q)
+      CHERT_LAUNCH("k_relax3", k_relax3, dim3(kFrontierBlocks), dim3(kFrontierThreads), 0, s, a,
+                   it + q, epoch);
+    e = hipMemcpyAsync(counts, a.counts + it + 1, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && a.far)
+      e = hipMemcpyAsync(counts + group, a.far_count + (epoch & 1), sizeof(int32_t),
+                         hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+    int empty = -1;
+    for (int q = 0; q < nb && empty < 0; ++q)
+      if (counts[q] == 0) empty = it + q + 1;
+    if (empty < 0) {
+      it += nb;
+      continue;
+    }
+    if (!a.far || counts[group] == 0) {
+      iters = empty;
+      break;
+    }
+    // next bucket: its frontier becomes iteration `empty`'s input
+    const int nfar = counts[group];
+    const unsigned fb = (unsigned)((nfar + 255) / 256 > 4096 ? 4096 : (nfar + 255) / 256);
+    const unsigned fmb = fb > 512 ? 512 : fb;  // few blocks: fewer global merges
+    CHERT_LAUNCH("k_far_min3", k_far_min3, dim3(fmb), dim3(256), 0, s, a, epoch);
+    CHERT_LAUNCH("k_far_thr3", k_far_thr3, dim3((a.n_prob + 255) / 256), dim3(256), 0, s, a,
+                 epoch);
+    CHERT_LAUNCH("k_far_split3", k_far_split3, dim3(fb), dim3(256), 0, s, a, epoch, empty);
+    ++epoch;
+    it = empty;
+  }
+  int32_t herr = 0;
+  unsigned long long hstats[2] = {0, 0};
+  e = hipMemcpyAsync(&herr, a.err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(hstats, a.stats, sizeof(hstats), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+  if (o->stats_host) {
+    chert_trace_stats* st = o->stats_host;
+    *st = chert_trace_stats{};
+    st->rounds[0] = iters < 0 ? P.max_iter : iters;
+    st->tile_visits[0] = (int64_t)hstats[0];
+    st->edge_relaxations[0] = (int64_t)hstats[1];
+  }
+  if (iters < 0) return fail(CHERT_ERR_NO_CONVERGENCE, "relaxation iteration cap reached");
+  if (herr) return fail(CHERT_ERR_INVALID_ARG, "class id out of range");
+  return CHERT_OK;
+}
+
+size_t trace_batch_3d_bytes(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o) {
+  Plan3 P;
+  if (make_plan3(jobs, n_jobs, o, &P) != CHERT_OK) return 0;
+  return P.total;
+}
+
+}  // namespace chert
