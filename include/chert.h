@@ -196,9 +196,11 @@ int chert_build_cache(const chert_cache_desc *d, const chert_class *classes_dev,
  * offsets with max(|ox|, |oy|, |oz|) <= radius (1..4) and gcd 1, ordered by
  * (oy, oz, ox) ascending, L_o = sqrt((ox hx)^2 + (oz hz)^2 + (oy hy)^2), and
  * the bin of o is the Fibonacci direction with the largest dot product with
- * o / L_o (lowest index on ties).  3D traces give tau_R and tau_I (with a
- * class map and a 3D cache); the relaxation is a node-frontier
- * label-correcting iteration with the same fixed point. */
+ * o / L_o (lowest index on ties).  3D traces (with a class map and a 3D
+ * cache) give every output of the 2D path by the same rules; the relaxation
+ * is a node-frontier label-correcting iteration with near/far buckets
+ * (chert_trace_opts.bucket_width) and the same fixed point; predecessors
+ * come from BFS layers over tight edges. */
 typedef struct chert_grid {
   int32_t dim;                 /* 2 or 3                                   */
   int32_t radius;              /* forward-star radius R, 1..8 (3D: 1..4)   */

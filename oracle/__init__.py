@@ -69,7 +69,7 @@ def lib():
         L.orc_fibonacci.argtypes = [i, P]
         L.orc_build_cache_3d.argtypes = [P, l, i, u, i, i, P, P]
         L.orc_star_3d.argtypes = [i, d, d, d, i, P, P, P, P, P]
-        L.orc_trace_3d.argtypes = [l, l, l, d, d, d, P, i, i, P, P, P, l, P, P, P, P]
+        L.orc_trace_3d.argtypes = [l, l, l, d, d, d, P, i, i, P, P, P, l, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -264,18 +264,19 @@ def star_3d(R, hx, hy, hz, N=N_FIB):
 
 
 def trace_3d(nx, ny, nz, hx, hy, hz, class_id, R, V, A, status, src, N=N_FIB):
-    """Dijkstra (tauR, tauI, predP, predA) on a 3D grid; node ix + nx (iy + ny iz)."""
+    """Dijkstra (tauR, tauI, predP, predA, tstar) on a 3D grid; node
+    ix + nx (iy + ny iz); t* folds the attenuation weights along predP."""
     n = nx * ny * nz
     cid = np.ascontiguousarray(class_id, dtype=np.int32).reshape(-1)
     assert cid.size == n
     V = np.ascontiguousarray(V, dtype=np.float64)
     A = np.ascontiguousarray(A, dtype=np.float64)
     st = np.ascontiguousarray(status, dtype=np.int32)
-    out = {k: np.zeros(n) for k in ("tauR", "tauI")}
+    out = {k: np.zeros(n) for k in ("tauR", "tauI", "tstar")}
     out.update({k: np.zeros(n, np.int32) for k in ("predP", "predA")})
     rc = lib().orc_trace_3d(nx, ny, nz, hx, hy, hz, _p(cid), R, N, _p(V), _p(A), _p(st),
                             int(src), _p(out["tauR"]), _p(out["tauI"]), _p(out["predP"]),
-                            _p(out["predA"]))
+                            _p(out["predA"]), _p(out["tstar"]))
     if rc:
         raise ValueError(f"orc_trace_3d failed rc={rc}")
     return out

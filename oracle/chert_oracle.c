@@ -1167,7 +1167,7 @@ int orc_star_3d(int R, double hx, double hy, double hz, int N, int32_t *ox,
 int orc_trace_3d(long nx, long ny, long nz, double hx, double hy, double hz,
                  const int32_t *class_id, int R, int N, const double *V,
                  const double *A, const int32_t *st, long src, double *tauR,
-                 double *tauI, int32_t *predP, int32_t *predA) {
+                 double *tauI, int32_t *predP, int32_t *predA, double *tstar) {
   long n = nx * ny * nz;
   if (src < 0 || src >= n || R < 1) return 1;
   int n_off = orc_star_3d(R, hx, hy, hz, N, NULL, NULL, NULL, NULL, NULL);
@@ -1191,12 +1191,27 @@ int orc_trace_3d(long nx, long ny, long nz, double hx, double hy, double hz,
   for (int field = 0; field < 2; ++field) {
     double *out_t = field ? tauI : tauR;
     int32_t *out_p = field ? predA : predP;
-    if (!out_t && !out_p) continue;
+    int want_ts = (field == 0 && tstar != NULL);
+    if (!out_t && !out_p && !want_ts) continue;
     if (dijkstra(&g, field, src, t)) { rc = 2; goto out; }
-    if (out_p) {
+    if (out_p || want_ts) {
       long nr = 0;
       predecessors(&g, field, src, t, pr, hp, ord, &nr);
-      memcpy(out_p, pr, sizeof(int32_t) * (size_t)n);
+      if (out_p) memcpy(out_p, pr, sizeof(int32_t) * (size_t)n);
+      if (want_ts) {
+        /* t*: attenuation folded along the propagation tree in BFS order */
+        for (long i = 0; i < n; ++i) tstar[i] = INFINITY;
+        tstar[src] = 0.0;
+        for (long q = 1; q < nr; ++q) {
+          long j = ord[q], i = pr[j];
+          long dx = (j % nx) - (i % nx), dy = (j / nx) % ny - (i / nx) % ny,
+               dz = j / (nx * ny) - i / (nx * ny);
+          int oo = -1;
+          for (int o = 0; o < n_off; ++o)
+            if (ox[o] == dx && oy[o] == dy && oz[o] == dz) { oo = o; break; }
+          tstar[j] = tstar[i] + edge_weight(&g, 1, i, j, oo);
+        }
+      }
     }
     if (out_t) memcpy(out_t, t, sizeof(double) * (size_t)n);
   }

@@ -61,8 +61,10 @@ struct Job3 {
 
 struct Prob3 {
   double* tau;
-  int32_t* stamp;   // near-frontier stamps (iteration numbers)
+  int32_t* stamp;   // near-frontier stamps (iteration numbers); hop counts later
   int32_t* fstamp;  // far-pile stamps (epoch numbers)
+  int32_t* pred;    // predecessors (nullable)
+  double* tstar;    // t* along this field's tree (nullable; propagation field)
   int job, field;
   int64_t src;
 };
@@ -87,7 +89,12 @@ struct R3 {
   double bucket;      // bucket width in units of wmin (0: one bucket)
   int64_t* far;       // [2][cap] far piles by epoch parity
   int32_t* far_count; // [2]
+  int32_t* seg;       // [max_iter + 2] start of each BFS layer in the order list
+  const int16_t* lut; // offset index of (dx, dy, dz), (2R+1)^3 entries, -1 if none
+  int R;
 };
+
+constexpr int32_t kHopUnset3 = 0x7fffffff;
 
 constexpr int kFrontierThreads = 256;
 constexpr int kFrontierBlocks = 4096;
@@ -261,11 +268,132 @@ __global__ void __launch_bounds__(kFrontierThreads) k_relax3(R3 a, int it, int e
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.stats[0], 1ull);
 }
 
+// ------------------------------------------------ predecessors and t* ---
+// Hop counts over tight edges (tau_i + w_ij == tau_j, bitwise) by BFS
+// layers: layer k holds the nodes at hop k, each node entered once (the
+// hop atomicMin is its own dedupe), all layers stored in order in one list.
+// pred_j is then the tight in-neighbour at hop_j - 1 with the smallest
+// offset index, and t* folds the attenuation weights along the propagation
+// predecessors layer by layer: the rule and the fold of the 2D path.
+
+__global__ void k_zero3(int32_t* counts, int32_t* seg, int n) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    counts[t] = 0;
+    seg[t] = 0;
+  }
+}
+
+// blockIdx.y = problem; only problems with predecessors take part
+__global__ void k_hop_init3(R3 a) {
+  const int p = blockIdx.y;
+  const Prob3 P = a.probs[p];
+  if (!P.pred) return;
+  const Job3 J = a.jobs[P.job];
+  const int64_t n = (int64_t)J.nx * J.ny * J.nz;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    P.stamp[j] = (j == P.src) ? 0 : kHopUnset3;
+    if (P.tstar) P.tstar[j] = (j == P.src) ? 0.0 : INFINITY;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    a.lists[atomicAdd(&a.counts[0], 1)] = ((int64_t)p << 32) | (int64_t)P.src;
+}
+
+__global__ void __launch_bounds__(kFrontierThreads) k_hop3(R3 a, int k) {
+  const int start = a.seg[k], cnt = a.counts[k];
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.seg[k + 1] = start + cnt;
+  if (cnt == 0) return;
+  const int64_t total = (int64_t)cnt * a.n_off;
+  int64_t* out = a.lists + start + cnt;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
+    const int64_t t = base + threadIdx.x;
+    bool want = false;
+    int64_t item_j = 0;
+    if (t < total) {
+      const int64_t f = t / a.n_off;
+      const int o = (int)(t - f * a.n_off);
+      const int64_t item = a.lists[start + f];
+      const int p = (int)(item >> 32);
+      const int i = (int)(item & 0xffffffffLL);
+      const Prob3 P = a.probs[p];
+      const Job3 J = a.jobs[P.job];
+      const int x = i % J.nx, r = i / J.nx, y = r % J.ny, z = r / J.ny;
+      const int X = x + a.ox[o], Y = y + a.oy[o], Z = z + a.oz[o];
+      if (X >= 0 && X < J.nx && Y >= 0 && Y < J.ny && Z >= 0 && Z < J.nz) {
+        const int j = X + J.nx * (Y + J.ny * Z);
+        const double tj = P.tau[j];
+        const int ci = J.cls[i], cj = J.cls[j];
+        if (tj < INFINITY && ci >= 0 && ci < J.K && cj >= 0 && cj < J.K) {
+          const double w = J.W[(((int64_t)P.field * J.K + ci) * J.K + cj) * a.n_off + o];
+          if (__dadd_rn(P.tau[i], w) == tj && atomicMin(&P.stamp[j], k + 1) > k + 1) {
+            want = true;
+            item_j = ((int64_t)p << 32) | (int64_t)j;
+          }
+        }
+      }
+    }
+    append64(want, item_j, out, &a.counts[k + 1]);
+  }
+}
+
+// blockIdx.y = problem
+__global__ void k_pred3(R3 a) {
+  const int p = blockIdx.y;
+  const Prob3 P = a.probs[p];
+  if (!P.pred) return;
+  const Job3 J = a.jobs[P.job];
+  const int64_t n = (int64_t)J.nx * J.ny * J.nz;
+  for (int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; jj < n;
+       jj += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)jj;
+    const int h = P.stamp[j];
+    int best = -1;
+    if (h != kHopUnset3 && h > 0) {
+      const int x = j % J.nx, r = j / J.nx, y = r % J.ny, z = r / J.ny;
+      const int cj = J.cls[j];
+      const double tj = P.tau[j];
+      for (int o = 0; o < a.n_off && best < 0; ++o) {
+        const int X = x - a.ox[o], Y = y - a.oy[o], Z = z - a.oz[o];
+        if (X < 0 || X >= J.nx || Y < 0 || Y >= J.ny || Z < 0 || Z >= J.nz) continue;
+        const int i = X + J.nx * (Y + J.ny * Z);
+        if (P.stamp[i] != h - 1) continue;
+        const int ci = J.cls[i];
+        if (ci < 0 || ci >= J.K || cj < 0 || cj >= J.K) continue;
+        const double w = J.W[(((int64_t)P.field * J.K + ci) * J.K + cj) * a.n_off + o];
+        if (__dadd_rn(P.tau[i], w) == tj) best = i;
+      }
+    }
+    P.pred[j] = best;
+  }
+}
+
+// t* of BFS layer k (k >= 1) of the propagation problems
+__global__ void k_tstar3(R3 a, int k) {
+  const int start = a.seg[k], cnt = a.counts[k];
+  const int side = 2 * a.R + 1;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
+    const int64_t item = a.lists[start + q];
+    const Prob3 P = a.probs[(int)(item >> 32)];
+    if (!P.tstar) continue;
+    const Job3 J = a.jobs[P.job];
+    const int j = (int)(item & 0xffffffffLL);
+    const int i = P.pred[j];
+    const int dx = j % J.nx - i % J.nx;
+    const int dy = (j / J.nx) % J.ny - (i / J.nx) % J.ny;
+    const int dz = j / (J.nx * J.ny) - i / (J.nx * J.ny);
+    const int o = a.lut[((dz + a.R) * side + (dy + a.R)) * side + (dx + a.R)];
+    const int ci = J.cls[i], cj = J.cls[j];
+    const double w = J.W[(((int64_t)1 * J.K + ci) * J.K + cj) * a.n_off + o];
+    P.tstar[j] = __dadd_rn(P.tstar[i], w);
+  }
+}
+
 struct Plan3 {
   int R = 0, n_off = 0, n_prob = 0, max_iter = 0;
   int64_t cap = 0;
   size_t off_star = 0, off_lcol = 0, off_jobs = 0, off_probs = 0, off_counts = 0, off_err = 0,
-         off_lists = 0, off_far = 0, off_thr = 0, total = 0;
+         off_lists = 0, off_far = 0, off_thr = 0, off_lut = 0, total = 0;
   std::vector<size_t> off_W, off_stamp;  // per job, per problem (near and far stamps)
 };
 
@@ -284,8 +412,9 @@ static int validate_job3(const chert_trace_job& j, uint32_t outs) {
       !isfinite(g->hy) || !isfinite(g->hz))
     return fail(CHERT_ERR_INVALID_ARG, "spacing must be positive");
   if (!g->class_id_dev) return fail(CHERT_ERR_UNSUPPORTED, "3D grids need a class map");
-  if (outs & ~(uint32_t)(CHERT_OUT_TAU_R | CHERT_OUT_TAU_I))
-    return fail(CHERT_ERR_UNSUPPORTED, "3D traces give tau_R and tau_I");
+  if ((outs & CHERT_OUT_PRED_P) && !j.pred_p_dev) return fail(CHERT_ERR_INVALID_ARG, "null pred_p");
+  if ((outs & CHERT_OUT_PRED_A) && !j.pred_a_dev) return fail(CHERT_ERR_INVALID_ARG, "null pred_a");
+  if ((outs & CHERT_OUT_TSTAR) && !j.tstar_dev) return fail(CHERT_ERR_INVALID_ARG, "null tstar");
   if (j.mode < 0 || j.mode > 2 || !(j.d->mode_mask & (1u << j.mode)))
     return fail(CHERT_ERR_INVALID_ARG, "mode not in the cache");
   if (!j.cache_dev) return fail(CHERT_ERR_INVALID_ARG, "null cache");
@@ -308,6 +437,13 @@ static int make_plan3(const chert_trace_job* jobs, int n_jobs, const chert_trace
     return fail(CHERT_ERR_INVALID_ARG, "bad output mask");
   if (!(o->bucket_width >= 0.0) || !isfinite(o->bucket_width))
     return fail(CHERT_ERR_INVALID_ARG, "bucket_width must be finite and >= 0");
+  if (outs & ~31u) return fail(CHERT_ERR_INVALID_ARG, "bad output mask");
+  if ((outs & CHERT_OUT_TSTAR) && !((outs & CHERT_OUT_TAU_R) && (outs & CHERT_OUT_PRED_P)))
+    return fail(CHERT_ERR_INVALID_ARG, "TSTAR needs TAU_R and PRED_P");
+  if ((outs & CHERT_OUT_PRED_P) && !(outs & CHERT_OUT_TAU_R))
+    return fail(CHERT_ERR_INVALID_ARG, "PRED_P needs TAU_R");
+  if ((outs & CHERT_OUT_PRED_A) && !(outs & CHERT_OUT_TAU_I))
+    return fail(CHERT_ERR_INVALID_ARG, "PRED_A needs TAU_I");
   for (int j = 0; j < n_jobs; ++j) {
     int rc = validate_job3(jobs[j], outs);
     if (rc) return rc;
@@ -341,7 +477,9 @@ static int make_plan3(const chert_trace_job* jobs, int n_jobs, const chert_trace
   P->off_probs = off;
   off += align256((size_t)P->n_prob * sizeof(Prob3));
   P->off_counts = off;
-  off += align256((size_t)(P->max_iter + 2) * sizeof(int32_t));
+  off += 2 * align256((size_t)(P->max_iter + 2) * sizeof(int32_t));  // counts, BFS layer starts
+  P->off_lut = off;
+  off += align256((size_t)9 * 9 * 9 * sizeof(int16_t));
   P->off_err = off;
   off += 256;
   P->off_W.clear();
@@ -409,9 +547,19 @@ int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
         q.job = j;
         q.field = field;
         q.src = J.src_nodes_host[i];
+        if (field == 0 && (outs & CHERT_OUT_PRED_P)) q.pred = J.pred_p_dev + (int64_t)i * n;
+        if (field == 1 && (outs & CHERT_OUT_PRED_A)) q.pred = J.pred_a_dev + (int64_t)i * n;
+        if (field == 0 && (outs & CHERT_OUT_TSTAR)) q.tstar = J.tstar_dev + (int64_t)i * n;
         pd.push_back(q);
       }
     }
+  }
+  std::vector<int16_t> lut(9 * 9 * 9, (int16_t)-1);
+  {
+    const int side = 2 * P.R + 1;
+    for (int q = 0; q < P.n_off; ++q)
+      lut[((star[2 * kMaxOffsets3 + q] + P.R) * side + (star[kMaxOffsets3 + q] + P.R)) * side +
+          (star[q] + P.R)] = (int16_t)q;
   }
   int32_t* dstar = (int32_t*)(ws + P.off_star);
   double* dL = (double*)(ws + P.off_lcol);
@@ -425,6 +573,9 @@ int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
     e = hipMemcpyAsync(djobs, jd.data(), jd.size() * sizeof(Job3), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(dprobs, pd.data(), pd.size() * sizeof(Prob3), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + P.off_lut, lut.data(), lut.size() * sizeof(int16_t),
+                       hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // host buffers are locals
   if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
 
@@ -465,6 +616,9 @@ int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
   a.wmin = a.thr_min + P.n_prob;
   a.bucket = o->bucket_width;
   a.far = o->bucket_width > 0.0 ? (int64_t*)(ws + P.off_far) : nullptr;
+  a.seg = a.counts + align256((size_t)(P.max_iter + 2) * sizeof(int32_t)) / sizeof(int32_t);
+  a.lut = (const int16_t*)(ws + P.off_lut);
+  a.R = P.R;
   CHERT_LAUNCH("k_clear3", k_clear3, dim3(64), dim3(256), 0, s, a.counts, P.max_iter + 2, a.err,
                a.stats);
   CHERT_LAUNCH("k_wmin_init3", k_wmin_init3, dim3(1), dim3(64), 0, s, a.wmin);
@@ -521,6 +675,27 @@ int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
     ++epoch;
     it = empty;
   }
+  int layers = 0;
+  if (iters >= 0 && (outs & (CHERT_OUT_PRED_P | CHERT_OUT_PRED_A | CHERT_OUT_TSTAR))) {
+    CHERT_LAUNCH("k_zero3", k_zero3, dim3(64), dim3(256), 0, s, a.counts, a.seg, P.max_iter + 2);
+    CHERT_LAUNCH("k_hop_init3", k_hop_init3, dim3(gx, (unsigned)a.n_prob), dim3(256), 0, s, a);
+    for (int k = 0; k < P.max_iter && layers == 0; k += group) {
+      const int nb = k + group > P.max_iter ? P.max_iter - k : group;
+      for (int q = 0; q < nb; ++q)
+        CHERT_LAUNCH("k_hop3", k_hop3, dim3(kFrontierBlocks), dim3(kFrontierThreads), 0, s, a,
+                     k + q);
+      e = hipMemcpyAsync(counts, a.counts + k + 1, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+      for (int q = 0; q < nb && layers == 0; ++q)
+        if (counts[q] == 0) layers = k + q + 1;
+    }
+    if (layers == 0) return fail(CHERT_ERR_NO_CONVERGENCE, "hop layers exceed the iteration cap");
+    CHERT_LAUNCH("k_pred3", k_pred3, dim3(gx, (unsigned)a.n_prob), dim3(256), 0, s, a);
+    if (outs & CHERT_OUT_TSTAR)
+      for (int k = 1; k < layers; ++k)
+        CHERT_LAUNCH("k_tstar3", k_tstar3, dim3(1024), dim3(256), 0, s, a, k);
+  }
   int32_t herr = 0;
   unsigned long long hstats[2] = {0, 0};
   e = hipMemcpyAsync(&herr, a.err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
@@ -531,6 +706,7 @@ int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
     chert_trace_stats* st = o->stats_host;
     *st = chert_trace_stats{};
     st->rounds[0] = iters < 0 ? P.max_iter : iters;
+    st->rounds[1] = layers;
     st->tile_visits[0] = (int64_t)hstats[0];
     st->edge_relaxations[0] = (int64_t)hstats[1];
   }

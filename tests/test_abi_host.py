@@ -169,8 +169,17 @@ def test_device_calls_validate_before_launch():
         C.chert_trace_field(d, _FakeTensor(), 3, g3, 0, [0], o, workspace_dev=_FakeTensor(), stream=0)
     assert e.value.code == 1
     d3 = C.cache_desc(dim=3, n_dirs=41253, modes=(0, 1))
-    with pytest.raises(C.ChertError) as e:  # 3D: predecessors and t* not traced
+    with pytest.raises(C.ChertError) as e:  # 3D: null outputs for the selected mask
         C.chert_trace_field(d3, _FakeTensor(), 3, g3, 0, [0], o, workspace_dev=_FakeTensor(),
+                            stream=0)
+    assert e.value.code == 1
+    with pytest.raises(C.ChertError) as e:  # 3D: t* without its inputs
+        C.chert_trace_field(d3, _FakeTensor(), 3, g3, 0, [0], C.trace_opts(C.OUT_TSTAR),
+                            workspace_dev=_FakeTensor(), stream=0)
+    assert e.value.code == 1
+    g3n = C.Grid(3, 3, 10, 10, 10, 5.0, 5.0, 5.0, None)
+    with pytest.raises(C.ChertError) as e:  # 3D needs a class map
+        C.chert_trace_field(d3, _FakeTensor(), 3, g3n, 0, [0], o, workspace_dev=_FakeTensor(),
                             stream=0)
     assert e.value.code == 2
     o3 = C.trace_opts(C.OUT_TAU_R | C.OUT_TAU_I)

@@ -97,19 +97,28 @@ def small3d():
     return m, cls, f, s
 
 
-def trace3(G, m, cache, desc, K, mode, bucket=0.0):
+def trace3(G, m, cache, desc, K, mode, bucket=0.0, full=False):
+    """tau_R, tau_I (and with full=True also t*, pred_P, pred_A) of every
+    source; returns numpy arrays and the counters."""
     Cm = C()
     cid = torch.from_numpy(np.ascontiguousarray(m.class_id.reshape(-1), dtype=np.int32)).to(G.DEV)
     g = Cm.make_grid3(m.nx, m.ny, m.nz, m.h, m.radius, cid)
     stats = Cm.TraceStats()
-    o = Cm.trace_opts(Cm.OUT_TAU_R | Cm.OUT_TAU_I, stats=stats, bucket_width=bucket)
+    outs = Cm.OUT_ALL if full else Cm.OUT_TAU_R | Cm.OUT_TAU_I
+    o = Cm.trace_opts(outs, stats=stats, bucket_width=bucket)
     S, n = len(m.sources), m.n_nodes
     tr = torch.empty((S, n), dtype=torch.float64, device=G.DEV)
     ti = torch.empty((S, n), dtype=torch.float64, device=G.DEV)
+    ts = torch.empty((S, n), dtype=torch.float64, device=G.DEV) if full else None
+    pp = torch.empty((S, n), dtype=torch.int32, device=G.DEV) if full else None
+    pa = torch.empty((S, n), dtype=torch.int32, device=G.DEV) if full else None
     ws = torch.empty(Cm.chert_trace_workspace_bytes(desc, K, g, S, o), dtype=torch.uint8,
                      device=G.DEV)
-    Cm.chert_trace_field(desc, cache, K, g, mode, m.sources, o, tr, ti, None, None, None, ws)
+    Cm.chert_trace_field(desc, cache, K, g, mode, m.sources, o, tr, ti, ts, pp, pa, ws)
     torch.cuda.synchronize()
+    if full:
+        return ({"tauR": tr.cpu().numpy(), "tauI": ti.cpu().numpy(), "tstar": ts.cpu().numpy(),
+                 "predP": pp.cpu().numpy(), "predA": pa.cpu().numpy()}, stats.as_dict())
     return tr.cpu().numpy(), ti.cpu().numpy(), stats.as_dict()
 
 
@@ -131,6 +140,27 @@ def test_trace_3d_imported_cache_bitwise(G, small3d, bucket):
                            f[1, mode], s[mode], src, N=400)
             assert np.array_equal(tr[si], o["tauR"]), (mode, si, int(np.sum(tr[si] != o["tauR"])))
             assert np.array_equal(ti[si], o["tauI"]), (mode, si)
+
+
+@pytest.mark.parametrize("bucket", [0.0, 16.0])
+def test_trace_3d_predecessors_and_tstar_bitwise(G, small3d, bucket):
+    """Predecessors of both fields (BFS hop over tight edges, then the
+    smallest offset index) and t* along the propagation tree equal the
+    oracle's, bitwise, for every source and both modes."""
+    Cm = C()
+    m, cls, f, s = small3d
+    K = cls.shape[0]
+    desc = Cm.cache_desc(dim=3, n_dirs=400, modes=(0, 1), n_sweep=360)
+    cache = G.import_cache(f, s, desc, K)
+    for mode in (0, 1):
+        g, st = trace3(G, m, cache, desc, K, mode, bucket, full=True)
+        print("mode", mode, st)
+        for si, src in enumerate(m.sources):
+            o = O.trace_3d(m.nx, m.ny, m.nz, m.h, m.h, m.h, m.class_id, m.radius, f[0, mode],
+                           f[1, mode], s[mode], src, N=400)
+            for key in ("tauR", "tauI", "tstar", "predP", "predA"):
+                assert np.array_equal(g[key][si], o[key]), (mode, si, key,
+                                                            int(np.sum(g[key][si] != o[key])))
 
 
 def test_trace_3d_end_to_end(G, small3d):

@@ -262,3 +262,27 @@ def test_homogeneous_isotropic_straight_rays_3d():
             t = t + L[q] / 3000.0
             j = (3 + k * ox[q]) + nx * ((3 + k * oy[q]) + ny * (3 + k * oz[q]))
             assert o["tauR"][j] == t
+
+
+def test_tstar_3d_is_the_fold_along_pred():
+    """t* of every reached node is the left-to-right fold of the attenuation
+    weights along its propagation raypath (eq 30 on the pred_P tree)."""
+    cls, f, s, cid = _small_3d(6, nx=6, ny=5, nz=4, R=2)
+    nx, ny, nz = 6, 5, 4
+    src = 7
+    o = O.trace_3d(nx, ny, nz, 10.0, 10.0, 10.0, cid, 2, f[0, 1], f[1, 1], s[1], src, N=800)
+    ox, oy, oz, L, b = O.star_3d(2, 10.0, 10.0, 10.0, 800)
+    A = f[1, 1]
+    for j in range(nx * ny * nz):
+        if not np.isfinite(o["tauR"][j]):
+            assert o["tstar"][j] == np.inf
+            continue
+        path = [j]
+        while path[-1] != src:
+            path.append(int(o["predP"][path[-1]]))
+        t = 0.0
+        for a, c in zip(path[::-1][:-1], path[::-1][1:]):
+            d = (c % nx - a % nx, (c // nx) % ny - (a // nx) % ny, c // (nx * ny) - a // (nx * ny))
+            q = [k for k in range(len(ox)) if (ox[k], oy[k], oz[k]) == d][0]
+            t = t + L[q] * (0.5 * (A[cid.flat[a], b[q]] + A[cid.flat[c], b[q]]))
+        assert t == o["tstar"][j]
