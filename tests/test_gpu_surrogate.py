@@ -405,3 +405,34 @@ def test_trained_surrogate_gain_over_plain(G, trained):
     fp, sp = G.cache_to_numpy(plain, desc, K)
     compare_to_plain(fw, sw, fp, sp, (1,))
     assert t_warm * 4.0 < t_plain
+
+
+@pytest.mark.slow
+def test_full_size_per_node_build_sampled(G, trained):
+    """The structurally complex model at full size (1701 x 351 nodes, qSV,
+    star bins): the surrogate-started per-node cache against the oracle's
+    plain solve at 24 sampled solid nodes (every column), within the cache
+    bar."""
+    from test_gpu_cache import compare_cache
+    C = _C()
+    blob, _ = trained
+    m = W.complex_2d()
+    rows = m.param_rows()
+    K = rows.shape[0]
+    classes = torch.empty((K, 13), dtype=torch.float64, device=G.DEV)
+    C.chert_classes_from_thomsen(torch.from_numpy(rows).to(G.DEV), classes)
+    sub = C.star_subset(5, m.hx, m.hz)
+    desc = C.cache_desc(modes=(1,), subset=sub)
+    warm, st = warm_build(G, classes, desc, blob, K)
+    print("full size", st)
+    assert st["jobs"] == K
+    f, s = C.cache_views(warm, desc, K)
+    rng = np.random.default_rng(77)
+    solid = np.flatnonzero(rows[:, 1] > 0)
+    pick = np.sort(rng.choice(solid, 24, replace=False))
+    idx = torch.from_numpy(pick).to(G.DEV)
+    fg = f[:, :, idx].cpu().numpy()
+    sg = s[:, idx].cpu().numpy()
+    cls_o = np.stack([O.class_from_thomsen(*r) for r in rows[pick]])
+    fo, so = O.build_cache_2d(cls_o, mode_mask=0b010, subset=sub)
+    compare_cache(fg, sg, fo, so, (1,))
