@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Hamiltonian solves/s; edge relaxations/s; shots/s, surrogate vs plain at 1e-4"
 HBM_PEAK_GBS = 8000.0
+LAUNCH_NAMES = ("per_round", "persistent", "frontier")
 FP64_PEAK_TFLOPS = 78.6
 FP64_VALU_PEAK_TOPS = 39.3  # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz, one op per lane-cycle
 
@@ -78,7 +79,10 @@ def parse():
                    help="relaxation tile shape (0 0 = library default)")
     p.add_argument("--push-group", type=int, default=0, help="offsets per push item (1, 2, 4)")
     p.add_argument("--launch", type=int, default=0,
-                   help="relaxation launch: 0 one launch per round, 1 persistent")
+                   help="relaxation launch: 0 tiles, one launch per round; 1 tiles, "
+                        "persistent; 2 node frontier")
+    p.add_argument("--bucket", type=float, default=0.0,
+                   help="node-frontier near/far bucket width (units of the smallest weight)")
     p.add_argument("--workload", choices=("layered", "complex2d", "shots", "3d"),
                    default="layered",
                    help="layered: the 5-layer model (default, the headline line); "
@@ -149,7 +153,8 @@ def main():
     grid = C.make_grid(m.nx, m.nz, m.hx, m.hz, m.radius, cid)
     stats = C.TraceStats()
     opts = C.trace_opts(C.OUT_ALL, tile_x=args.tile[0], tile_z=args.tile[1], stats=stats,
-                        push_group=args.push_group, launch=args.launch)
+                        push_group=args.push_group, launch=args.launch,
+                        bucket_width=args.bucket)
     S = len(m.sources)
     n = m.n_nodes
     outs = {mode: dict(
@@ -235,10 +240,11 @@ def main():
     # tau tiles, class ids and the class-pair weight table on chip, so its
     # algorithmic work is FP64 VALU: one add and one compare per useful edge
     # relaxation; peak = 78.6 TFLOP/s (FMA counted twice) / 2 = 39.3 T ops/s.
-    if dom.startswith("k_relax"):
-        phase = {"k_relax_tau": 0, "k_relax_hop": 1, "k_relax_tstar": 2,
-                 "k_relax_persist_tau": 0, "k_relax_persist_hop": 1,
-                 "k_relax_persist_tstar": 2}[dom]
+    phases = {"k_relax_tau": 0, "k_relax_hop": 1, "k_relax_tstar": 2,
+              "k_relax_persist_tau": 0, "k_relax_persist_hop": 1, "k_relax_persist_tstar": 2,
+              "k_front_relax": 0, "k_front_hop": 1, "k_front_tstar": 2}
+    if dom in phases:
+        phase = phases[dom]
         useful_phase = {0: edges_per_step, 1: edges_per_step, 2: E * len(m.modes)}[phase]
         per_launch_ops = 2.0 * useful_phase / kernels[dom]["launches_per_step"]
         achieved = per_launch_ops / (kernels[dom]["avg_us"] * 1e-6) / 1e12
@@ -450,7 +456,8 @@ def run_complex(args):
     # 4. per-node traveltimes through the surrogate-started cache
     grid = C.make_grid(m.nx, m.nz, m.hx, m.hz, m.radius, None)
     stats = C.TraceStats()
-    opts = C.trace_opts(C.OUT_TAU_R | C.OUT_TAU_I | C.OUT_TSTAR | C.OUT_PRED_P, stats=stats)
+    opts = C.trace_opts(C.OUT_TAU_R | C.OUT_TAU_I | C.OUT_TSTAR | C.OUT_PRED_P, stats=stats,
+                        launch=args.launch, bucket_width=args.bucket)
     S = len(m.sources)
     tr = {k: torch.empty((S, n), dtype=torch.float64, device=dev) for k in ("r", "i", "t")}
     pp = torch.empty((S, n), dtype=torch.int32, device=dev)
@@ -595,10 +602,10 @@ def run_shots(args):
     probe_ms = C.chert_trace_autotune(b, opts, ws, stream=stream)
     res["autotune"] = {"s": time.perf_counter() - t0, "probe_ms": probe_ms,
                        "tile": [opts.tile_x, opts.tile_z], "push_group": opts.push_group,
-                       "launch": ["per_round", "persistent"][opts.launch]}
+                       "launch": LAUNCH_NAMES[opts.launch], "bucket_width": opts.bucket_width}
     stats = C.TraceStats()
     opts_s = C.trace_opts(outs, opts.tile_x, opts.tile_z, push_group=opts.push_group,
-                          launch=opts.launch, stats=stats)
+                          launch=opts.launch, bucket_width=opts.bucket_width, stats=stats)
     ev = _events(torch, stream)
     C.chert_trace_batch(b, opts_s, ws, stream=stream)
     t_eager = _elapsed(torch, ev, stream)

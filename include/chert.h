@@ -219,7 +219,9 @@ enum {
 };
 
 /* Work counters of one trace call, per phase (0 = traveltimes, 1 = hop
- * counts for the predecessors, 2 = t*). */
+ * counts for the predecessors, 2 = t*).  Frontier runs fill rounds[0] =
+ * iterations, rounds[1] = BFS layers, tile_visits[0] = iterations that had
+ * work and edge_relaxations[0] = (frontier node, offset) pairs examined. */
 typedef struct chert_trace_stats {
   int32_t rounds[3];           /* relaxation rounds until no tile changed   */
   int32_t reserved;
@@ -239,8 +241,17 @@ typedef struct chert_trace_stats {
  *               barrier (bounded wait: a stalled barrier fails the call with
  *               CHERT_ERR_HIP instead of hanging); the host waits only at
  *               the end, and the launch sequence can be captured into a
- *               graph (chert_trace_graph_create). */
-enum { CHERT_LAUNCH_PER_ROUND = 0, CHERT_LAUNCH_PERSISTENT = 1 };
+ *               graph (chert_trace_graph_create);
+ *   FRONTIER    no tiles: the node-frontier label-correcting iteration of
+ *               the 3D path (one thread per (frontier node, offset), 64-bit
+ *               atomicMin on the head, optional near/far buckets), one launch
+ *               per iteration, the host checking the frontier sizes every 8
+ *               iterations; predecessors from BFS layers over tight edges.
+ *               3D batches always run this way, whatever `launch` says.
+ * In per-node mode (no class map) the relaxation may read an edge's weight
+ * from either endpoint's row; both hold the same value because a cache
+ * stores direction d + n_dirs/2 as the exact copy of d. */
+enum { CHERT_LAUNCH_PER_ROUND = 0, CHERT_LAUNCH_PERSISTENT = 1, CHERT_LAUNCH_FRONTIER = 2 };
 
 typedef struct chert_trace_opts {
   uint32_t outputs;   /* CHERT_OUT_* bits.  TSTAR needs TAU_R and PRED_P;
@@ -249,11 +260,13 @@ typedef struct chert_trace_opts {
   int32_t tile_z;     /* relaxation tile height in nodes (0 = default 32)  */
   int32_t max_rounds; /* cap on relaxation rounds per phase (0 = default)  */
   int32_t push_group; /* star offsets per push work item: 1, 2 or 4 (0 = 2) */
-  int32_t launch;     /* CHERT_LAUNCH_PER_ROUND (0) or _PERSISTENT (1)      */
-  double bucket_width;/* 3D frontier: near/far bucket width in units of the
-                         batch's smallest positive edge weight of the field;
-                         0 = one bucket (every improvement is relaxed next
-                         iteration).  Ignored in 2D.  Must be >= 0.        */
+  int32_t launch;     /* CHERT_LAUNCH_PER_ROUND (0), _PERSISTENT (1) or
+                         _FRONTIER (2)                                     */
+  double bucket_width;/* frontier iteration: near/far bucket width in units
+                         of the batch's smallest positive edge weight of the
+                         field; 0 = one bucket (every improvement is relaxed
+                         next iteration).  Ignored by the tile launches.
+                         Must be >= 0.                                     */
   chert_trace_stats *stats_host; /* nullable: filled when the call returns */
 } chert_trace_opts;
 
@@ -311,10 +324,11 @@ int chert_trace_batch(const chert_trace_job *jobs, int32_t n_jobs,
 
 /* Autotuner of the relaxation's launch parameters for a given batch.  The
  * fixed point does not depend on them (every candidate gives the same
- * fields); only the time does.  2D candidates: tile shapes 32x32, 64x16,
- * 16x64, 32x16, 16x32, 128x8; push groups 1, 2, 4; per-round and persistent
- * launch.  3D candidates: frontier bucket widths 0 (one bucket), 4, 16, 32,
- * 64, 128, 256 (units of the smallest edge weight).  Each is timed (HIP events,
+ * fields); only the time does.  Candidates: in 3D the frontier iteration
+ * with bucket widths 0 (one bucket), 4, 16, 32, 64, 128, 256 (units of the
+ * smallest edge weight); in 2D the frontier with widths 0, 16, 64 and the
+ * tiles 32x32, 64x16, 16x64, 32x16, 16x32, 128x8 with push groups 1, 2, 4,
+ * per-round and persistent launch.  Each is timed (HIP events,
  * second of two runs) on a probe batch made of the first source of every
  * job; the fastest is written into o->tile_x, tile_z, push_group, launch and
  * bucket_width (other fields are kept) and its probe time into *best_ms

@@ -27,7 +27,7 @@ FIELDS = ("V", "A", "Q", "rx", "rz", "thR", "thI", "res")
 NF = len(FIELDS)
 OUT_TAU_R, OUT_TAU_I, OUT_TSTAR, OUT_PRED_P, OUT_PRED_A = 1, 2, 4, 8, 16
 OUT_ALL = 31
-LAUNCH_PER_ROUND, LAUNCH_PERSISTENT = 0, 1
+LAUNCH_PER_ROUND, LAUNCH_PERSISTENT, LAUNCH_FRONTIER = 0, 1, 2
 
 EXPORTS = (
     "chert_class_from_thomsen", "chert_classes_from_thomsen", "chert_cache_layout_of",
@@ -335,8 +335,9 @@ def make_grid(nx, nz, hx, hz, radius, class_id_dev):
 def trace_opts(outputs=OUT_ALL, tile_x=0, tile_z=0, max_rounds=0, stats=None, push_group=0,
                launch=0, bucket_width=0.0):
     """stats: a TraceStats to fill (kept referenced by the returned options);
-    launch: LAUNCH_PER_ROUND or LAUNCH_PERSISTENT; bucket_width: 3D
-    near/far frontier bucket width (units of the smallest edge weight)."""
+    launch: LAUNCH_PER_ROUND, LAUNCH_PERSISTENT (2D tiles) or LAUNCH_FRONTIER
+    (node frontier; always used in 3D); bucket_width: near/far bucket width
+    of the frontier iteration (units of the smallest edge weight)."""
     o = TraceOpts(outputs, tile_x, tile_z, max_rounds, push_group, launch, float(bucket_width),
                   ctypes.addressof(stats) if stats is not None else None)
     o._stats = stats

@@ -3,7 +3,7 @@
 Per-file floating-point contraction:
   - cache_build.hip: FMA contraction allowed (the local solve is compared
     with a tolerance);
-  - trace.hip, abi_host.cpp: -ffp-contract=off, so edge weights, traveltime
+  - trace.hip, frontier.hip, abi_host.cpp: -ffp-contract=off, so edge weights, traveltime
     sums and the host-side star lengths are plain IEEE operations.
 """
 from __future__ import annotations
@@ -25,7 +25,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 SOURCES = [
     ("cache_build.hip", ["-ffp-contract=fast"]),
     ("trace.hip", ["-ffp-contract=off"]),
-    ("trace3d.hip", ["-ffp-contract=off"]),
+    ("frontier.hip", ["-ffp-contract=off"]),
     ("surrogate.hip", ["-ffp-contract=fast"]),
     ("abi_host.cpp", ["-ffp-contract=off", "-x", "hip"]),
 ]

@@ -55,6 +55,20 @@ int star_2d(int R, double hx, double hz, int n_dirs, int32_t* ox, int32_t* oz, d
   return n;
 }
 
+int star_columns(const chert_cache_desc* d, const int32_t* bin, int n_off, int32_t* col) {
+  for (int o = 0; o < n_off; ++o) {
+    int c = bin[o];
+    if (d->n_subset) {
+      c = -1;
+      for (int q = 0; q < d->n_subset; ++q)
+        if (d->subset_host[q] == bin[o]) c = q;
+    }
+    if (c < 0) return fail(CHERT_ERR_INVALID_ARG, "the cache lacks a direction of the star");
+    col[o] = c;
+  }
+  return CHERT_OK;
+}
+
 void fibonacci(int N, double* f) {
   const double ga = M_PI * (3.0 - sqrt(5.0));
   for (int i = 0; i < N; ++i) {

@@ -35,13 +35,32 @@ void fibonacci(int N, double* f);
 int star_3d(int R, double hx, double hy, double hz, int N, int32_t* ox, int32_t* oy, int32_t* oz,
             double* L, int32_t* bin);
 
-// 3D batches (trace3d.hip): all jobs on 3D grids
+// Cache column of every offset's bin (bin[o] in 0..n_dirs-1): the bin itself,
+// or its position in the cache's direction subset.  INVALID_ARG when the
+// subset lacks a bin.
+int star_columns(const chert_cache_desc* d, const int32_t* bin, int n_off, int32_t* col);
+
+// Node-frontier batches (frontier.hip): every 3D batch, and 2D batches run
+// with CHERT_LAUNCH_FRONTIER.
 inline bool is_3d_batch(const chert_trace_job* jobs, int n_jobs) {
   return jobs && n_jobs > 0 && jobs[0].g && jobs[0].g->dim == 3;
 }
-int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o,
-                   void* workspace_dev, size_t workspace_bytes, hipStream_t s);
-size_t trace_batch_3d_bytes(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o);
+inline bool uses_frontier(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o) {
+  return is_3d_batch(jobs, n_jobs) || (o && o->launch == CHERT_LAUNCH_FRONTIER);
+}
+int trace_batch_frontier(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o,
+                         void* workspace_dev, size_t workspace_bytes, hipStream_t s);
+size_t trace_batch_frontier_bytes(const chert_trace_job* jobs, int n_jobs,
+                                  const chert_trace_opts* o);
+
+// 2D job checks shared by the tile and frontier paths (trace.hip).
+int validate_job_2d(const chert_trace_job& j, uint32_t outs);
+// Per-node weight table of a 2D job: W[f][j][o] = the edge j - o -> j
+// (eqs 27-30), +inf off the grid or on an unusable entry (trace.hip).
+int enqueue_weights_node_2d(double* W, int nx, int nz, int n_off, const int32_t* ox_dev,
+                            const int32_t* oz_dev, const double* L_dev, const int32_t* col_dev,
+                            int n_cols, const double* V, const double* A, const int32_t* st,
+                            hipStream_t s);
 
 // Kernel timing for chert_prof_*: returns a slot (or -1 when profiling is
 // off) after recording a start event on the stream; prof_end records the stop.

@@ -1,6 +1,24 @@
-// 3D traveltimes (eq 31 on a 3D forward star) for gfx950: a node-frontier
-// label-correcting iteration with near/far buckets.  See trace.hip for the
-// 2D tile relaxation; both reach the same fixed point as Dijkstra.
+// Node-frontier label-correcting traveltimes (eq 31 over the forward star,
+// edge costs of eqs 27-30) for gfx950.  Every 3D batch runs here, and so do
+// 2D batches that ask for CHERT_LAUNCH_FRONTIER; trace.hip holds the 2D tile
+// relaxation.  Both reach the fixed point Dijkstra reaches from the same
+// weights.
+//
+// Iteration it relaxes every out-edge of the (problem, node) items whose
+// traveltime dropped in iteration it - 1, one thread per (item, offset): an
+// improved head is claimed with a 64-bit atomicMin on the bits of the
+// (non-negative) double, stamped so that it enters the next frontier once,
+// and appended with one atomic per wavefront (ballot + prefix count).  With
+// near/far buckets an improvement at or above the problem's threshold waits
+// in a far pile until the near frontier is empty.
+//
+// Predecessors (eq 33): hop counts over tight edges (tau_i + w_ij == tau_j,
+// bitwise) by BFS layers: layer k holds the nodes at hop k, each node
+// entered once (the hop atomicMin is its own dedupe), all layers stored in
+// order in one list.  pred_j is the tight in-neighbour at hop_j - 1 with the
+// smallest offset index, and t* folds the attenuation weights along the
+// propagation predecessors layer by layer: the rule and the fold of the tile
+// path.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -19,11 +37,16 @@ __device__ __forceinline__ unsigned long long dbits(double x) {
 }
 
 constexpr int kFieldR = 0;
+constexpr int32_t kHopUnsetF = 0x7fffffff;
+constexpr int kFrontierThreads = 256;
+constexpr int kFrontierBlocks = 4096;
+constexpr int kLutSide = 2 * kMaxRadius + 1;  // (dx, dy, dz) -> offset index table side
 
 // W[f][ki][kj][o] (eqs 28-30 in this operation order, no contraction) from a
-// mode's slice of a 3D cache: the column of offset o is its Fibonacci bin
-__global__ void k_weights3(double* W, int K, int n_off, const double* V, const double* A,
-                           const int32_t* st, int n_cols, const double* L, const int32_t* col) {
+// mode's slice of a cache: col[o] is the cache column of offset o's bin
+__global__ void k_front_weights(double* W, int K, int n_off, const double* V, const double* A,
+                                const int32_t* st, int n_cols, const double* L,
+                                const int32_t* col) {
   const int64_t total = 2LL * K * K * n_off;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
@@ -44,22 +67,47 @@ __global__ void k_weights3(double* W, int K, int n_off, const double* V, const d
   }
 }
 
-// Node-frontier label-correcting relaxation on 3D grids (eq 31 over the 3D
-// forward star, edge costs of eqs 27-30 from a Fibonacci-direction cache).
-// Iteration it relaxes every out-edge of the (problem, node) items whose
-// traveltime dropped in iteration it - 1: an improved head is claimed with a
-// 64-bit atomicMin on the bits of the (non-negative) double, stamped so that
-// it enters the next frontier once, and appended with one atomic per
-// wavefront (ballot + prefix count).  The fixed point is the same minimum
-// over path folds as the 2D tiles and Dijkstra reach.
-
-struct Job3 {
-  int nx, ny, nz, K;
-  const int32_t* cls;
-  const double* W;  // [2][K][K][n_off]
+struct JobF {
+  int nx, ny, nz, K;  // ny = 1 in 2D
+  int per_node;       // one cache row per node, weights per (node, offset)
+  int pad;
+  int64_t n;          // nodes
+  const int32_t* cls; // class map (class mode)
+  const double* W;    // class mode [2][K][K][n_off]; per node [2][n][n_off] where
+                      // row j, offset o holds the edge j - o -> j
 };
 
-struct Prob3 {
+// Weight of the edge i -> j = i + o read from the tail's row.  Per node that
+// is row i at the reversed offset (the star is symmetric: index n_off-1-o is
+// -o), whose entry is the edge j -> i: equal bitwise, since the cache holds
+// direction d + n_dirs/2 as the exact copy of d and L_o is even in o.  False
+// when a class id is out of range.
+__device__ __forceinline__ bool w_tail(const JobF& J, int n_off, int field, int i, int j, int o,
+                                       double* w) {
+  if (J.per_node) {
+    *w = J.W[((int64_t)field * J.n + i) * n_off + (n_off - 1 - o)];
+    return true;
+  }
+  const int ci = J.cls[i], cj = J.cls[j];
+  if (ci < 0 || ci >= J.K || cj < 0 || cj >= J.K) return false;
+  *w = J.W[(((int64_t)field * J.K + ci) * J.K + cj) * n_off + o];
+  return true;
+}
+
+// The same edge read from the head's row.
+__device__ __forceinline__ bool w_head(const JobF& J, int n_off, int field, int i, int j, int o,
+                                       double* w) {
+  if (J.per_node) {
+    *w = J.W[((int64_t)field * J.n + j) * n_off + o];
+    return true;
+  }
+  const int ci = J.cls[i], cj = J.cls[j];
+  if (ci < 0 || ci >= J.K || cj < 0 || cj >= J.K) return false;
+  *w = J.W[(((int64_t)field * J.K + ci) * J.K + cj) * n_off + o];
+  return true;
+}
+
+struct ProbF {
   double* tau;
   int32_t* stamp;   // near-frontier stamps (iteration numbers); hop counts later
   int32_t* fstamp;  // far-pile stamps (epoch numbers)
@@ -69,9 +117,9 @@ struct Prob3 {
   int64_t src;
 };
 
-struct R3 {
-  const Job3* jobs;
-  const Prob3* probs;
+struct RF {
+  const JobF* jobs;
+  const ProbF* probs;
   int n_prob, n_off;
   const int32_t* ox;
   const int32_t* oy;
@@ -81,8 +129,6 @@ struct R3 {
   int32_t* counts;  // [max_iter + 2] frontier size of each iteration
   int32_t* err;
   unsigned long long* stats;  // [0] iterations run with work, [1] edges examined
-  // near/far buckets: an improvement at or above the problem's threshold
-  // waits in the far pile until the near frontier is empty
   double* thr;        // [n_prob] current threshold (+inf: one bucket)
   double* thr_min;    // [n_prob] far-pile minimum (scratch of the split)
   double* wmin;       // [2] smallest positive edge weight per field
@@ -93,11 +139,6 @@ struct R3 {
   const int16_t* lut; // offset index of (dx, dy, dz), (2R+1)^3 entries, -1 if none
   int R;
 };
-
-constexpr int32_t kHopUnset3 = 0x7fffffff;
-
-constexpr int kFrontierThreads = 256;
-constexpr int kFrontierBlocks = 4096;
 
 __device__ __forceinline__ void append64(bool flag, int64_t item, int64_t* list, int32_t* count) {
   const unsigned long long b = __ballot(flag);
@@ -110,8 +151,16 @@ __device__ __forceinline__ void append64(bool flag, int64_t item, int64_t* list,
   if (flag) list[base + __popcll(b & ((1ull << lane) - 1ull))] = item;
 }
 
-__global__ void k_clear3(int32_t* counts, int n_counts, int32_t* err,
-                         unsigned long long* stats) {
+// neighbour of node i at offset o (sign +1) or -o (sign -1); -1 outside the grid
+__device__ __forceinline__ int step(const JobF& J, const RF& a, int i, int o, int sign) {
+  const int x = i % J.nx, r = i / J.nx, y = r % J.ny, z = r / J.ny;
+  const int X = x + sign * a.ox[o], Y = y + sign * a.oy[o], Z = z + sign * a.oz[o];
+  if (X < 0 || X >= J.nx || Y < 0 || Y >= J.ny || Z < 0 || Z >= J.nz) return -1;
+  return X + J.nx * (Y + J.ny * Z);
+}
+
+__global__ void k_front_clear(int32_t* counts, int n_counts, int32_t* err,
+                              unsigned long long* stats) {
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n_counts; t += gridDim.x * blockDim.x)
     counts[t] = 0;
   if (blockIdx.x == 0 && threadIdx.x < 4) {
@@ -122,11 +171,10 @@ __global__ void k_clear3(int32_t* counts, int n_counts, int32_t* err,
 }
 
 // blockIdx.y = problem: tau = inf (0 at the source), stamps 0, source queued
-__global__ void k_init3(R3 a) {
+__global__ void k_front_init(RF a) {
   const int p = blockIdx.y;
-  const Prob3 P = a.probs[p];
-  const Job3 J = a.jobs[P.job];
-  const int64_t n = (int64_t)J.nx * J.ny * J.nz;
+  const ProbF P = a.probs[p];
+  const int64_t n = a.jobs[P.job].n;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * blockDim.x) {
     P.tau[j] = (j == P.src) ? 0.0 : INFINITY;
@@ -142,7 +190,7 @@ __global__ void k_init3(R3 a) {
 }
 
 // smallest positive finite weight of each field over a job's table
-__global__ void k_wmin3(const double* W, int64_t per_field, double* wmin) {
+__global__ void k_front_wmin(const double* W, int64_t per_field, double* wmin) {
   const int f = blockIdx.y;
   double m = INFINITY;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < per_field;
@@ -154,7 +202,7 @@ __global__ void k_wmin3(const double* W, int64_t per_field, double* wmin) {
   if (__lane_id() == 0 && m < INFINITY) atomicMin((unsigned long long*)&wmin[f], dbits(m));
 }
 
-__global__ void k_wmin_init3(double* wmin) {
+__global__ void k_front_wmin_init(double* wmin) {
   if (threadIdx.x < 2) wmin[threadIdx.x] = INFINITY;
 }
 
@@ -162,7 +210,7 @@ __global__ void k_wmin_init3(double* wmin) {
 // minima in LDS (few problems, many items: one global atomic per problem
 // and block instead of one per item)
 constexpr int kFarMinLds = 2048;
-__global__ void __launch_bounds__(256) k_far_min3(R3 a, int epoch) {
+__global__ void __launch_bounds__(256) k_front_far_min(RF a, int epoch) {
   __shared__ unsigned long long s_min[kFarMinLds];
   const bool lds = a.n_prob <= kFarMinLds;
   if (lds)
@@ -184,7 +232,7 @@ __global__ void __launch_bounds__(256) k_far_min3(R3 a, int epoch) {
 }
 
 // split, step 2: thresholds move to the far minimum plus one bucket
-__global__ void k_far_thr3(R3 a, int epoch) {
+__global__ void k_front_far_thr(RF a, int epoch) {
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < a.n_prob; p += gridDim.x * blockDim.x) {
     const double m = a.thr_min[p];
     if (m < INFINITY) a.thr[p] = m + a.bucket * a.wmin[a.probs[p].field];
@@ -195,7 +243,7 @@ __global__ void k_far_thr3(R3 a, int epoch) {
 
 // split, step 3: far items under the new threshold form iteration it's
 // frontier; the rest move to the next epoch's pile
-__global__ void k_far_split3(R3 a, int epoch, int it) {
+__global__ void k_front_far_split(RF a, int epoch, int it) {
   const int nf = a.far_count[epoch & 1];
   const int64_t* fl = a.far + (int64_t)(epoch & 1) * a.cap;
   int64_t* fo = a.far + (int64_t)((epoch + 1) & 1) * a.cap;
@@ -208,7 +256,7 @@ __global__ void k_far_split3(R3 a, int epoch, int it) {
       item = fl[q];
       const int p = (int)(item >> 32);
       const int64_t j = item & 0xffffffffLL;
-      const Prob3 P = a.probs[p];
+      const ProbF P = a.probs[p];
       if (P.tau[j] < a.thr[p]) near = atomicExch(&P.stamp[j], it) != it;
       else far = atomicExch(&P.fstamp[j], epoch + 2) != epoch + 2;
     }
@@ -217,7 +265,7 @@ __global__ void k_far_split3(R3 a, int epoch, int it) {
   }
 }
 
-__global__ void __launch_bounds__(kFrontierThreads) k_relax3(R3 a, int it, int epoch) {
+__global__ void __launch_bounds__(kFrontierThreads) k_front_relax(RF a, int it, int epoch) {
   const int n_near = a.counts[it];
   if (n_near == 0) return;
   const int64_t total = (int64_t)n_near * a.n_off;
@@ -236,17 +284,14 @@ __global__ void __launch_bounds__(kFrontierThreads) k_relax3(R3 a, int it, int e
       const int64_t item = lin[f];
       const int p = (int)(item >> 32);
       const int i = (int)(item & 0xffffffffLL);
-      const Prob3 P = a.probs[p];
-      const Job3 J = a.jobs[P.job];
-      const int x = i % J.nx, r = i / J.nx, y = r % J.ny, z = r / J.ny;
-      const int X = x + a.ox[o], Y = y + a.oy[o], Z = z + a.oz[o];
-      if (X >= 0 && X < J.nx && Y >= 0 && Y < J.ny && Z >= 0 && Z < J.nz) {
-        const int j = X + J.nx * (Y + J.ny * Z);
-        const int ci = J.cls[i], cj = J.cls[j];
-        if (ci < 0 || ci >= J.K || cj < 0 || cj >= J.K) {
+      const ProbF P = a.probs[p];
+      const JobF J = a.jobs[P.job];
+      const int j = step(J, a, i, o, 1);
+      double w;
+      if (j >= 0) {
+        if (!w_tail(J, a.n_off, P.field, i, j, o, &w)) {
           *a.err = 1;
         } else {
-          const double w = J.W[(((int64_t)P.field * J.K + ci) * J.K + cj) * a.n_off + o];
           const double cand = __dadd_rn(P.tau[i], w);
           if (cand < P.tau[j]) {
             const unsigned long long old =
@@ -269,14 +314,8 @@ __global__ void __launch_bounds__(kFrontierThreads) k_relax3(R3 a, int it, int e
 }
 
 // ------------------------------------------------ predecessors and t* ---
-// Hop counts over tight edges (tau_i + w_ij == tau_j, bitwise) by BFS
-// layers: layer k holds the nodes at hop k, each node entered once (the
-// hop atomicMin is its own dedupe), all layers stored in order in one list.
-// pred_j is then the tight in-neighbour at hop_j - 1 with the smallest
-// offset index, and t* folds the attenuation weights along the propagation
-// predecessors layer by layer: the rule and the fold of the 2D path.
 
-__global__ void k_zero3(int32_t* counts, int32_t* seg, int n) {
+__global__ void k_front_zero(int32_t* counts, int32_t* seg, int n) {
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     counts[t] = 0;
     seg[t] = 0;
@@ -284,22 +323,21 @@ __global__ void k_zero3(int32_t* counts, int32_t* seg, int n) {
 }
 
 // blockIdx.y = problem; only problems with predecessors take part
-__global__ void k_hop_init3(R3 a) {
+__global__ void k_front_hop_init(RF a) {
   const int p = blockIdx.y;
-  const Prob3 P = a.probs[p];
+  const ProbF P = a.probs[p];
   if (!P.pred) return;
-  const Job3 J = a.jobs[P.job];
-  const int64_t n = (int64_t)J.nx * J.ny * J.nz;
+  const int64_t n = a.jobs[P.job].n;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * blockDim.x) {
-    P.stamp[j] = (j == P.src) ? 0 : kHopUnset3;
+    P.stamp[j] = (j == P.src) ? 0 : kHopUnsetF;
     if (P.tstar) P.tstar[j] = (j == P.src) ? 0.0 : INFINITY;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0)
     a.lists[atomicAdd(&a.counts[0], 1)] = ((int64_t)p << 32) | (int64_t)P.src;
 }
 
-__global__ void __launch_bounds__(kFrontierThreads) k_hop3(R3 a, int k) {
+__global__ void __launch_bounds__(kFrontierThreads) k_front_hop(RF a, int k) {
   const int start = a.seg[k], cnt = a.counts[k];
   if (blockIdx.x == 0 && threadIdx.x == 0) a.seg[k + 1] = start + cnt;
   if (cnt == 0) return;
@@ -316,20 +354,16 @@ __global__ void __launch_bounds__(kFrontierThreads) k_hop3(R3 a, int k) {
       const int64_t item = a.lists[start + f];
       const int p = (int)(item >> 32);
       const int i = (int)(item & 0xffffffffLL);
-      const Prob3 P = a.probs[p];
-      const Job3 J = a.jobs[P.job];
-      const int x = i % J.nx, r = i / J.nx, y = r % J.ny, z = r / J.ny;
-      const int X = x + a.ox[o], Y = y + a.oy[o], Z = z + a.oz[o];
-      if (X >= 0 && X < J.nx && Y >= 0 && Y < J.ny && Z >= 0 && Z < J.nz) {
-        const int j = X + J.nx * (Y + J.ny * Z);
+      const ProbF P = a.probs[p];
+      const JobF J = a.jobs[P.job];
+      const int j = step(J, a, i, o, 1);
+      double w;
+      if (j >= 0) {
         const double tj = P.tau[j];
-        const int ci = J.cls[i], cj = J.cls[j];
-        if (tj < INFINITY && ci >= 0 && ci < J.K && cj >= 0 && cj < J.K) {
-          const double w = J.W[(((int64_t)P.field * J.K + ci) * J.K + cj) * a.n_off + o];
-          if (__dadd_rn(P.tau[i], w) == tj && atomicMin(&P.stamp[j], k + 1) > k + 1) {
-            want = true;
-            item_j = ((int64_t)p << 32) | (int64_t)j;
-          }
+        if (tj < INFINITY && w_tail(J, a.n_off, P.field, i, j, o, &w) &&
+            __dadd_rn(P.tau[i], w) == tj && atomicMin(&P.stamp[j], k + 1) > k + 1) {
+          want = true;
+          item_j = ((int64_t)p << 32) | (int64_t)j;
         }
       }
     }
@@ -338,30 +372,23 @@ __global__ void __launch_bounds__(kFrontierThreads) k_hop3(R3 a, int k) {
 }
 
 // blockIdx.y = problem
-__global__ void k_pred3(R3 a) {
+__global__ void k_front_pred(RF a) {
   const int p = blockIdx.y;
-  const Prob3 P = a.probs[p];
+  const ProbF P = a.probs[p];
   if (!P.pred) return;
-  const Job3 J = a.jobs[P.job];
-  const int64_t n = (int64_t)J.nx * J.ny * J.nz;
-  for (int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; jj < n;
+  const JobF J = a.jobs[P.job];
+  for (int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; jj < J.n;
        jj += (int64_t)gridDim.x * blockDim.x) {
     const int j = (int)jj;
     const int h = P.stamp[j];
     int best = -1;
-    if (h != kHopUnset3 && h > 0) {
-      const int x = j % J.nx, r = j / J.nx, y = r % J.ny, z = r / J.ny;
-      const int cj = J.cls[j];
+    if (h != kHopUnsetF && h > 0) {
       const double tj = P.tau[j];
       for (int o = 0; o < a.n_off && best < 0; ++o) {
-        const int X = x - a.ox[o], Y = y - a.oy[o], Z = z - a.oz[o];
-        if (X < 0 || X >= J.nx || Y < 0 || Y >= J.ny || Z < 0 || Z >= J.nz) continue;
-        const int i = X + J.nx * (Y + J.ny * Z);
-        if (P.stamp[i] != h - 1) continue;
-        const int ci = J.cls[i];
-        if (ci < 0 || ci >= J.K || cj < 0 || cj >= J.K) continue;
-        const double w = J.W[(((int64_t)P.field * J.K + ci) * J.K + cj) * a.n_off + o];
-        if (__dadd_rn(P.tau[i], w) == tj) best = i;
+        const int i = step(J, a, j, o, -1);
+        if (i < 0 || P.stamp[i] != h - 1) continue;
+        double w;
+        if (w_head(J, a.n_off, P.field, i, j, o, &w) && __dadd_rn(P.tau[i], w) == tj) best = i;
       }
     }
     P.pred[j] = best;
@@ -369,33 +396,39 @@ __global__ void k_pred3(R3 a) {
 }
 
 // t* of BFS layer k (k >= 1) of the propagation problems
-__global__ void k_tstar3(R3 a, int k) {
+__global__ void k_front_tstar(RF a, int k) {
   const int start = a.seg[k], cnt = a.counts[k];
   const int side = 2 * a.R + 1;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
     const int64_t item = a.lists[start + q];
-    const Prob3 P = a.probs[(int)(item >> 32)];
+    const ProbF P = a.probs[(int)(item >> 32)];
     if (!P.tstar) continue;
-    const Job3 J = a.jobs[P.job];
+    const JobF J = a.jobs[P.job];
     const int j = (int)(item & 0xffffffffLL);
     const int i = P.pred[j];
+    if (i < 0) continue;  // only if the two rows of a per-node edge disagree
     const int dx = j % J.nx - i % J.nx;
     const int dy = (j / J.nx) % J.ny - (i / J.nx) % J.ny;
     const int dz = j / (J.nx * J.ny) - i / (J.nx * J.ny);
     const int o = a.lut[((dz + a.R) * side + (dy + a.R)) * side + (dx + a.R)];
-    const int ci = J.cls[i], cj = J.cls[j];
-    const double w = J.W[(((int64_t)1 * J.K + ci) * J.K + cj) * a.n_off + o];
+    if (o < 0) continue;
+    double w = INFINITY;
+    w_head(J, a.n_off, 1, i, j, o, &w);
     P.tstar[j] = __dadd_rn(P.tstar[i], w);
   }
 }
 
-struct Plan3 {
-  int R = 0, n_off = 0, n_prob = 0, max_iter = 0;
+// ------------------------------------------------------------------ plan --
+
+struct PlanF {
+  int dim = 0, R = 0, n_off = 0, n_prob = 0, max_iter = 0;
   int64_t cap = 0;
   size_t off_star = 0, off_lcol = 0, off_jobs = 0, off_probs = 0, off_counts = 0, off_err = 0,
          off_lists = 0, off_far = 0, off_thr = 0, off_lut = 0, total = 0;
   std::vector<size_t> off_W, off_stamp;  // per job, per problem (near and far stamps)
 };
+
+static bool per_node_job(const chert_trace_job& j) { return j.g->dim == 2 && !j.g->class_id_dev; }
 
 static int validate_job3(const chert_trace_job& j, uint32_t outs) {
   chert_cache_layout lay;
@@ -428,10 +461,11 @@ static int validate_job3(const chert_trace_job& j, uint32_t outs) {
   return CHERT_OK;
 }
 
-static int make_plan3(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o,
-                      Plan3* P) {
+static int make_plan_f(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o,
+                       PlanF* P) {
   if (!jobs || n_jobs < 1) return fail(CHERT_ERR_INVALID_ARG, "need at least one job");
   if (!o) return fail(CHERT_ERR_INVALID_ARG, "null options");
+  if (!jobs[0].g) return fail(CHERT_ERR_INVALID_ARG, "null grid");
   const uint32_t outs = o->outputs;
   if (outs == 0 || !(outs & (CHERT_OUT_TAU_R | CHERT_OUT_TAU_I)))
     return fail(CHERT_ERR_INVALID_ARG, "bad output mask");
@@ -444,14 +478,17 @@ static int make_plan3(const chert_trace_job* jobs, int n_jobs, const chert_trace
     return fail(CHERT_ERR_INVALID_ARG, "PRED_P needs TAU_R");
   if ((outs & CHERT_OUT_PRED_A) && !(outs & CHERT_OUT_TAU_I))
     return fail(CHERT_ERR_INVALID_ARG, "PRED_A needs TAU_I");
+  P->dim = jobs[0].g->dim;
   for (int j = 0; j < n_jobs; ++j) {
-    int rc = validate_job3(jobs[j], outs);
+    int rc = P->dim == 3 ? validate_job3(jobs[j], outs) : validate_job_2d(jobs[j], outs);
     if (rc) return rc;
     if (jobs[j].g->radius != jobs[0].g->radius)
       return fail(CHERT_ERR_INVALID_ARG, "all jobs of a batch need the same radius");
   }
   P->R = jobs[0].g->radius;
-  P->n_off = star_3d(P->R, 1.0, 1.0, 1.0, 2, nullptr, nullptr, nullptr, nullptr, nullptr);
+  P->n_off = P->dim == 3
+                 ? star_3d(P->R, 1.0, 1.0, 1.0, 2, nullptr, nullptr, nullptr, nullptr, nullptr)
+                 : star_2d(P->R, 1.0, 1.0, 4, nullptr, nullptr, nullptr, nullptr);
   const int per = ((outs & CHERT_OUT_TAU_R) ? 1 : 0) + ((outs & CHERT_OUT_TAU_I) ? 1 : 0);
   int64_t span = 0;
   P->n_prob = 0;
@@ -473,19 +510,22 @@ static int make_plan3(const chert_trace_job* jobs, int n_jobs, const chert_trace
   P->off_lcol = off;
   off += align256((size_t)n_jobs * P->n_off * (sizeof(double) + sizeof(int32_t)));
   P->off_jobs = off;
-  off += align256((size_t)n_jobs * sizeof(Job3));
+  off += align256((size_t)n_jobs * sizeof(JobF));
   P->off_probs = off;
-  off += align256((size_t)P->n_prob * sizeof(Prob3));
+  off += align256((size_t)P->n_prob * sizeof(ProbF));
   P->off_counts = off;
   off += 2 * align256((size_t)(P->max_iter + 2) * sizeof(int32_t));  // counts, BFS layer starts
   P->off_lut = off;
-  off += align256((size_t)9 * 9 * 9 * sizeof(int16_t));
+  off += align256((size_t)kLutSide * kLutSide * kLutSide * sizeof(int16_t));
   P->off_err = off;
   off += 256;
   P->off_W.clear();
   for (int j = 0; j < n_jobs; ++j) {
     P->off_W.push_back(off);
-    off += align256((size_t)2 * jobs[j].n_classes * jobs[j].n_classes * P->n_off * sizeof(double));
+    const chert_grid* g = jobs[j].g;
+    const size_t rows = per_node_job(jobs[j]) ? (size_t)(g->nx * g->nz)
+                                              : (size_t)jobs[j].n_classes * jobs[j].n_classes;
+    off += align256((size_t)2 * rows * P->n_off * sizeof(double));
   }
   P->off_stamp.clear();
   for (int j = 0; j < n_jobs; ++j) {
@@ -505,41 +545,55 @@ static int make_plan3(const chert_trace_job* jobs, int n_jobs, const chert_trace
   return CHERT_OK;
 }
 
-int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o,
-                   void* workspace_dev, size_t workspace_bytes, hipStream_t s) {
-  Plan3 P;
-  int rc = make_plan3(jobs, n_jobs, o, &P);
+// ---------------------------------------------------------------- driver --
+
+int trace_batch_frontier(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o,
+                         void* workspace_dev, size_t workspace_bytes, hipStream_t s) {
+  PlanF P;
+  int rc = make_plan_f(jobs, n_jobs, o, &P);
   if (rc) return rc;
   if (!workspace_dev || workspace_bytes < P.total)
     return fail(CHERT_ERR_INVALID_ARG, "workspace too small");
   uint8_t* ws = (uint8_t*)workspace_dev;
   const uint32_t outs = o->outputs;
-  // star (shared) and per-job lengths and cache columns
+  // star (shared offsets; oy = 0 in 2D), per-job lengths and cache columns
   std::vector<int32_t> star((size_t)3 * kMaxOffsets3, 0);
   std::vector<uint8_t> lcol((size_t)n_jobs * P.n_off * (sizeof(double) + sizeof(int32_t)));
   double* hL = (double*)lcol.data();
   int32_t* hcol = (int32_t*)(hL + (size_t)n_jobs * P.n_off);
+  std::vector<int32_t> bin(P.n_off);
   for (int j = 0; j < n_jobs; ++j) {
     const chert_grid* g = jobs[j].g;
-    star_3d(P.R, g->hx, g->hy, g->hz, jobs[j].d->n_dirs, star.data(), star.data() + kMaxOffsets3,
-            star.data() + 2 * kMaxOffsets3, hL + (size_t)j * P.n_off,
-            hcol + (size_t)j * P.n_off);
+    int32_t* ox = star.data();
+    int32_t* oy = star.data() + kMaxOffsets3;
+    int32_t* oz = star.data() + 2 * kMaxOffsets3;
+    double* L = hL + (size_t)j * P.n_off;
+    int32_t* col = hcol + (size_t)j * P.n_off;
+    if (P.dim == 3) {
+      star_3d(P.R, g->hx, g->hy, g->hz, jobs[j].d->n_dirs, ox, oy, oz, L, col);
+    } else {
+      star_2d(P.R, g->hx, g->hz, jobs[j].d->n_dirs, ox, oz, L, bin.data());
+      rc = star_columns(jobs[j].d, bin.data(), P.n_off, col);
+      if (rc) return rc;
+    }
   }
-  std::vector<Job3> jd(n_jobs);
-  std::vector<Prob3> pd;
+  std::vector<JobF> jd(n_jobs);
+  std::vector<ProbF> pd;
   for (int j = 0; j < n_jobs; ++j) {
     const chert_trace_job& J = jobs[j];
     jd[j].nx = (int)J.g->nx;
-    jd[j].ny = (int)J.g->ny;
+    jd[j].ny = P.dim == 3 ? (int)J.g->ny : 1;
     jd[j].nz = (int)J.g->nz;
     jd[j].K = (int)J.n_classes;
+    jd[j].per_node = per_node_job(J) ? 1 : 0;
+    jd[j].n = (int64_t)jd[j].nx * jd[j].ny * jd[j].nz;
     jd[j].cls = J.g->class_id_dev;
     jd[j].W = (const double*)(ws + P.off_W[j]);
-    const int64_t n = J.g->nx * J.g->ny * J.g->nz;
+    const int64_t n = jd[j].n;
     for (int i = 0; i < J.n_src; ++i) {
       for (int field = 0; field < 2; ++field) {
         if (!(outs & (field ? CHERT_OUT_TAU_I : CHERT_OUT_TAU_R))) continue;
-        Prob3 q{};
+        ProbF q{};
         q.tau = (field ? J.tau_i_dev : J.tau_r_dev) + (int64_t)i * n;
         q.stamp = (int32_t*)(ws + P.off_stamp[pd.size()]);
         q.fstamp = (int32_t*)(ws + P.off_stamp[pd.size()] +
@@ -554,7 +608,7 @@ int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
       }
     }
   }
-  std::vector<int16_t> lut(9 * 9 * 9, (int16_t)-1);
+  std::vector<int16_t> lut((size_t)kLutSide * kLutSide * kLutSide, (int16_t)-1);
   {
     const int side = 2 * P.R + 1;
     for (int q = 0; q < P.n_off; ++q)
@@ -564,15 +618,15 @@ int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
   int32_t* dstar = (int32_t*)(ws + P.off_star);
   double* dL = (double*)(ws + P.off_lcol);
   int32_t* dcol = (int32_t*)(dL + (size_t)n_jobs * P.n_off);
-  Job3* djobs = (Job3*)(ws + P.off_jobs);
-  Prob3* dprobs = (Prob3*)(ws + P.off_probs);
+  JobF* djobs = (JobF*)(ws + P.off_jobs);
+  ProbF* dprobs = (ProbF*)(ws + P.off_probs);
   hipError_t e = hipMemcpyAsync(dstar, star.data(), star.size() * sizeof(int32_t),
                                 hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(dL, lcol.data(), lcol.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(djobs, jd.data(), jd.size() * sizeof(Job3), hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(djobs, jd.data(), jd.size() * sizeof(JobF), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(dprobs, pd.data(), pd.size() * sizeof(Prob3), hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(dprobs, pd.data(), pd.size() * sizeof(ProbF), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ws + P.off_lut, lut.data(), lut.size() * sizeof(int16_t),
                        hipMemcpyHostToDevice, s);
@@ -585,19 +639,29 @@ int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
     chert_cache_layout_of(J.d, J.n_classes, &lay);
     const uint8_t* cache = (const uint8_t*)J.cache_dev;
     const int64_t K = J.n_classes;
-    const int n_cols = J.d->n_dirs;
+    const int n_cols = J.d->n_subset ? J.d->n_subset : J.d->n_dirs;
     const int64_t ent = 3 * K * (int64_t)n_cols;
     const int64_t mslice = (int64_t)J.mode * K * n_cols;
     const double* fields = (const double*)(cache + lay.fields_offset);
-    int64_t tw = 2 * K * K * P.n_off;
-    int64_t blocks = (tw + 255) / 256;
-    CHERT_LAUNCH("k_weights3", k_weights3, dim3((unsigned)(blocks > 65536 ? 65536 : blocks)),
-                 dim3(256), 0, s, (double*)(ws + P.off_W[j]), (int)K, P.n_off,
-                 fields + CHERT_F_V * ent + mslice, fields + CHERT_F_A * ent + mslice,
-                 (const int32_t*)(cache + lay.status_offset) + mslice, n_cols,
-                 dL + (size_t)j * P.n_off, dcol + (size_t)j * P.n_off);
+    const double* Vm = fields + CHERT_F_V * ent + mslice;
+    const double* Am = fields + CHERT_F_A * ent + mslice;
+    const int32_t* Sm = (const int32_t*)(cache + lay.status_offset) + mslice;
+    double* W = (double*)(ws + P.off_W[j]);
+    if (jd[j].per_node) {
+      rc = enqueue_weights_node_2d(W, jd[j].nx, jd[j].nz, P.n_off, dstar,
+                                   dstar + 2 * kMaxOffsets3, dL + (size_t)j * P.n_off,
+                                   dcol + (size_t)j * P.n_off, n_cols, Vm, Am, Sm, s);
+      if (rc) return rc;
+    } else {
+      const int64_t tw = 2 * K * K * P.n_off;
+      const int64_t blocks = (tw + 255) / 256;
+      CHERT_LAUNCH("k_front_weights", k_front_weights,
+                   dim3((unsigned)(blocks > 65536 ? 65536 : blocks)), dim3(256), 0, s, W, (int)K,
+                   P.n_off, Vm, Am, Sm, n_cols, dL + (size_t)j * P.n_off,
+                   dcol + (size_t)j * P.n_off);
+    }
   }
-  R3 a{};
+  RF a{};
   a.jobs = djobs;
   a.probs = dprobs;
   a.n_prob = (int)pd.size();
@@ -619,24 +683,23 @@ int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
   a.seg = a.counts + align256((size_t)(P.max_iter + 2) * sizeof(int32_t)) / sizeof(int32_t);
   a.lut = (const int16_t*)(ws + P.off_lut);
   a.R = P.R;
-  CHERT_LAUNCH("k_clear3", k_clear3, dim3(64), dim3(256), 0, s, a.counts, P.max_iter + 2, a.err,
-               a.stats);
-  CHERT_LAUNCH("k_wmin_init3", k_wmin_init3, dim3(1), dim3(64), 0, s, a.wmin);
+  CHERT_LAUNCH("k_front_clear", k_front_clear, dim3(64), dim3(256), 0, s, a.counts,
+               P.max_iter + 2, a.err, a.stats);
+  CHERT_LAUNCH("k_front_wmin_init", k_front_wmin_init, dim3(1), dim3(64), 0, s, a.wmin);
   if (a.far) {
     for (int j = 0; j < n_jobs; ++j) {
-      const int64_t per_field = jobs[j].n_classes * jobs[j].n_classes * (int64_t)P.n_off;
-      int64_t blocks = (per_field + 255) / 256;
-      CHERT_LAUNCH("k_wmin3", k_wmin3, dim3((unsigned)(blocks > 1024 ? 1024 : blocks), 2),
+      const int64_t rows = jd[j].per_node ? jd[j].n : jobs[j].n_classes * jobs[j].n_classes;
+      const int64_t per_field = rows * (int64_t)P.n_off;
+      const int64_t blocks = (per_field + 255) / 256;
+      CHERT_LAUNCH("k_front_wmin", k_front_wmin, dim3((unsigned)(blocks > 1024 ? 1024 : blocks), 2),
                    dim3(256), 0, s, (const double*)(ws + P.off_W[j]), per_field, a.wmin);
     }
   }
   int64_t max_nodes = 0;
-  for (int j = 0; j < n_jobs; ++j) {
-    const int64_t n = jobs[j].g->nx * jobs[j].g->ny * jobs[j].g->nz;
-    if (n > max_nodes) max_nodes = n;
-  }
+  for (int j = 0; j < n_jobs; ++j)
+    if (jd[j].n > max_nodes) max_nodes = jd[j].n;
   const unsigned gx = (unsigned)((max_nodes + 255) / 256 > 1024 ? 1024 : (max_nodes + 255) / 256);
-  CHERT_LAUNCH("k_init3", k_init3, dim3(gx, (unsigned)a.n_prob), dim3(256), 0, s, a);
+  CHERT_LAUNCH("k_front_init", k_front_init, dim3(gx, (unsigned)a.n_prob), dim3(256), 0, s, a);
   // iterations in groups of 8 between host checks of the frontier sizes;
   // an empty near frontier with a non-empty far pile starts the next bucket
   const int group = 8;
@@ -645,8 +708,8 @@ int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
   for (int it = 0; it < P.max_iter && iters < 0;) {
     const int nb = it + group > P.max_iter ? P.max_iter - it : group;
     for (int q = 0; q < nb; ++q)
-      CHERT_LAUNCH("k_relax3", k_relax3, dim3(kFrontierBlocks), dim3(kFrontierThreads), 0, s, a,
-                   it + q, epoch);
+      CHERT_LAUNCH("k_front_relax", k_front_relax, dim3(kFrontierBlocks), dim3(kFrontierThreads),
+                   0, s, a, it + q, epoch);
     e = hipMemcpyAsync(counts, a.counts + it + 1, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && a.far)
       e = hipMemcpyAsync(counts + group, a.far_count + (epoch & 1), sizeof(int32_t),
@@ -668,22 +731,25 @@ int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
     const int nfar = counts[group];
     const unsigned fb = (unsigned)((nfar + 255) / 256 > 4096 ? 4096 : (nfar + 255) / 256);
     const unsigned fmb = fb > 512 ? 512 : fb;  // few blocks: fewer global merges
-    CHERT_LAUNCH("k_far_min3", k_far_min3, dim3(fmb), dim3(256), 0, s, a, epoch);
-    CHERT_LAUNCH("k_far_thr3", k_far_thr3, dim3((a.n_prob + 255) / 256), dim3(256), 0, s, a,
-                 epoch);
-    CHERT_LAUNCH("k_far_split3", k_far_split3, dim3(fb), dim3(256), 0, s, a, epoch, empty);
+    CHERT_LAUNCH("k_front_far_min", k_front_far_min, dim3(fmb), dim3(256), 0, s, a, epoch);
+    CHERT_LAUNCH("k_front_far_thr", k_front_far_thr, dim3((a.n_prob + 255) / 256), dim3(256), 0,
+                 s, a, epoch);
+    CHERT_LAUNCH("k_front_far_split", k_front_far_split, dim3(fb), dim3(256), 0, s, a, epoch,
+                 empty);
     ++epoch;
     it = empty;
   }
   int layers = 0;
   if (iters >= 0 && (outs & (CHERT_OUT_PRED_P | CHERT_OUT_PRED_A | CHERT_OUT_TSTAR))) {
-    CHERT_LAUNCH("k_zero3", k_zero3, dim3(64), dim3(256), 0, s, a.counts, a.seg, P.max_iter + 2);
-    CHERT_LAUNCH("k_hop_init3", k_hop_init3, dim3(gx, (unsigned)a.n_prob), dim3(256), 0, s, a);
+    CHERT_LAUNCH("k_front_zero", k_front_zero, dim3(64), dim3(256), 0, s, a.counts, a.seg,
+                 P.max_iter + 2);
+    CHERT_LAUNCH("k_front_hop_init", k_front_hop_init, dim3(gx, (unsigned)a.n_prob), dim3(256), 0,
+                 s, a);
     for (int k = 0; k < P.max_iter && layers == 0; k += group) {
       const int nb = k + group > P.max_iter ? P.max_iter - k : group;
       for (int q = 0; q < nb; ++q)
-        CHERT_LAUNCH("k_hop3", k_hop3, dim3(kFrontierBlocks), dim3(kFrontierThreads), 0, s, a,
-                     k + q);
+        CHERT_LAUNCH("k_front_hop", k_front_hop, dim3(kFrontierBlocks), dim3(kFrontierThreads), 0,
+                     s, a, k + q);
       e = hipMemcpyAsync(counts, a.counts + k + 1, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
@@ -691,10 +757,10 @@ int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
         if (counts[q] == 0) layers = k + q + 1;
     }
     if (layers == 0) return fail(CHERT_ERR_NO_CONVERGENCE, "hop layers exceed the iteration cap");
-    CHERT_LAUNCH("k_pred3", k_pred3, dim3(gx, (unsigned)a.n_prob), dim3(256), 0, s, a);
+    CHERT_LAUNCH("k_front_pred", k_front_pred, dim3(gx, (unsigned)a.n_prob), dim3(256), 0, s, a);
     if (outs & CHERT_OUT_TSTAR)
       for (int k = 1; k < layers; ++k)
-        CHERT_LAUNCH("k_tstar3", k_tstar3, dim3(1024), dim3(256), 0, s, a, k);
+        CHERT_LAUNCH("k_front_tstar", k_front_tstar, dim3(1024), dim3(256), 0, s, a, k);
   }
   int32_t herr = 0;
   unsigned long long hstats[2] = {0, 0};
@@ -715,9 +781,10 @@ int trace_batch_3d(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
   return CHERT_OK;
 }
 
-size_t trace_batch_3d_bytes(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o) {
-  Plan3 P;
-  if (make_plan3(jobs, n_jobs, o, &P) != CHERT_OK) return 0;
+size_t trace_batch_frontier_bytes(const chert_trace_job* jobs, int n_jobs,
+                                  const chert_trace_opts* o) {
+  PlanF P;
+  if (make_plan_f(jobs, n_jobs, o, &P) != CHERT_OK) return 0;
   return P.total;
 }
 

@@ -177,6 +177,18 @@ __global__ void k_weights_node(double* W, int nx, int nz, int n_off, const int32
   }
 }
 
+int enqueue_weights_node_2d(double* W, int nx, int nz, int n_off, const int32_t* ox_dev,
+                            const int32_t* oz_dev, const double* L_dev, const int32_t* col_dev,
+                            int n_cols, const double* V, const double* A, const int32_t* st,
+                            hipStream_t s) {
+  const int64_t tw = (int64_t)nx * nz * n_off;
+  const int64_t blocks = (tw + 255) / 256;
+  CHERT_LAUNCH("k_weights_node", k_weights_node, dim3((unsigned)(blocks > 65536 ? 65536 : blocks)),
+               dim3(256), 0, s, W, nx, nz, n_off, ox_dev, oz_dev, L_dev, col_dev, n_cols, V, A,
+               st);
+  return CHERT_OK;
+}
+
 // ---------------------------------------------------------------- init ---
 
 // blockIdx.y = problem; x strides over its nodes
@@ -1014,7 +1026,7 @@ struct Plan {
   int w_lds_doubles = 0;
 };
 
-static int validate_job(const chert_trace_job& j, uint32_t outs) {
+int validate_job_2d(const chert_trace_job& j, uint32_t outs) {
   chert_cache_layout lay;
   int rc = chert_cache_layout_of(j.d, j.n_classes, &lay);
   if (rc) return rc;
@@ -1071,7 +1083,7 @@ static int make_plan(const chert_trace_job* jobs, int n_jobs, const chert_trace_
   int rc = validate_opts(o);
   if (rc) return rc;
   for (int j = 0; j < n_jobs; ++j) {
-    rc = validate_job(jobs[j], o->outputs);
+    rc = validate_job_2d(jobs[j], o->outputs);
     if (rc) return rc;
     if (jobs[j].g->radius != jobs[0].g->radius)
       return fail(CHERT_ERR_INVALID_ARG, "all jobs of a batch need the same radius");
@@ -1233,18 +1245,8 @@ static int prepare(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
     const chert_cache_desc* d = jobs[j].d;
     star_2d(P.R, g->hx, g->hz, d->n_dirs, star.data(), star.data() + kMaxOffsets,
             hL + (size_t)j * kMaxOffsets, hbin + (size_t)j * kMaxOffsets);
-    // cache column of every offset's bin
-    for (int o = 0; o < P.n_off; ++o) {
-      const int b = hbin[(size_t)j * kMaxOffsets + o];
-      int c = b;
-      if (d->n_subset) {
-        c = -1;
-        for (int q = 0; q < d->n_subset; ++q)
-          if (d->subset_host[q] == b) c = q;
-      }
-      if (c < 0) return fail(CHERT_ERR_INVALID_ARG, "the cache lacks a direction of the star");
-      hcol[(size_t)j * kMaxOffsets + o] = c;
-    }
+    rc = star_columns(d, hbin + (size_t)j * kMaxOffsets, P.n_off, hcol + (size_t)j * kMaxOffsets);
+    if (rc) return rc;
   }
   int32_t* dox = (int32_t*)(ws + P.off_star);
   int32_t* doz = dox + kMaxOffsets;
@@ -1385,13 +1387,10 @@ static int enqueue(const Prepared& Q, const chert_trace_job* jobs, int n_jobs,
     const double* Am = fields + CHERT_F_A * ent + mslice;
     const int32_t* Sm = (const int32_t*)(cache + lay.status_offset) + mslice;
     if (Q.jd[j].per_node) {
-      int64_t tw = P.nodes[j] * P.n_off;
-      int64_t blocks = (tw + 255) / 256;
-      CHERT_LAUNCH("k_weights_node", k_weights_node,
-                   dim3((unsigned)(blocks > 65536 ? 65536 : blocks)), dim3(256), 0, s,
-                   (double*)(ws + P.off_W[j]), Q.jd[j].nx, Q.jd[j].nz, P.n_off, Q.dox, Q.doz,
-                   Q.dL + (size_t)j * kMaxOffsets, Q.dcol + (size_t)j * kMaxOffsets, n_cols, Vm,
-                   Am, Sm);
+      int rc = enqueue_weights_node_2d((double*)(ws + P.off_W[j]), Q.jd[j].nx, Q.jd[j].nz,
+                                       P.n_off, Q.dox, Q.doz, Q.dL + (size_t)j * kMaxOffsets,
+                                       Q.dcol + (size_t)j * kMaxOffsets, n_cols, Vm, Am, Sm, s);
+      if (rc) return rc;
     } else {
       int64_t tw = 2 * K * K * P.n_off;
       int64_t blocks = (tw + 255) / 256;
@@ -1491,8 +1490,8 @@ static int finish(const Prepared& Q, const chert_trace_opts* o, hipStream_t s, i
 
 static int trace_batch(const chert_trace_job* jobs, int n_jobs, const chert_trace_opts* o,
                        void* workspace_dev, size_t workspace_bytes, hipStream_t s) {
-  if (is_3d_batch(jobs, n_jobs))
-    return trace_batch_3d(jobs, n_jobs, o, workspace_dev, workspace_bytes, s);
+  if (uses_frontier(jobs, n_jobs, o))
+    return trace_batch_frontier(jobs, n_jobs, o, workspace_dev, workspace_bytes, s);
   Prepared Q;
   int rc = prepare(jobs, n_jobs, o, workspace_dev, workspace_bytes, s, &Q);
   if (rc) return rc;
@@ -1529,7 +1528,7 @@ using namespace chert;
 
 extern "C" size_t chert_trace_batch_workspace_bytes(const chert_trace_job* jobs, int32_t n_jobs,
                                                     const chert_trace_opts* o) {
-  if (is_3d_batch(jobs, n_jobs)) return trace_batch_3d_bytes(jobs, n_jobs, o);
+  if (uses_frontier(jobs, n_jobs, o)) return trace_batch_frontier_bytes(jobs, n_jobs, o);
   Plan P;
   if (make_plan(jobs, n_jobs, o, &P) != CHERT_OK) return 0;
   return P.total;
@@ -1552,7 +1551,7 @@ extern "C" size_t chert_trace_workspace_bytes(const chert_cache_desc* d, int64_t
   int32_t dummy_i = 0;
   chert_trace_job j = single_job(d, &dummy_d, n_classes, g, mode, src.data(), n_src, &dummy_d,
                                  &dummy_d, &dummy_d, &dummy_i, &dummy_i);
-  if (g->dim == 3) return trace_batch_3d_bytes(&j, 1, o);
+  if (uses_frontier(&j, 1, o)) return trace_batch_frontier_bytes(&j, 1, o);
   Plan P;
   if (make_plan(&j, 1, o, &P) != CHERT_OK) return 0;
   return P.total;
@@ -1579,21 +1578,23 @@ const int kTuneLaunch[] = {CHERT_LAUNCH_PER_ROUND, CHERT_LAUNCH_PERSISTENT};
 }  // namespace
 
 const double kTuneBuckets[] = {0.0, 4.0, 16.0, 32.0, 64.0, 128.0, 256.0};
+const double kTuneBuckets2D[] = {0.0, 16.0, 64.0};  // 2D: the tiles usually win
 
 extern "C" size_t chert_trace_autotune_workspace_bytes(const chert_trace_job* jobs,
                                                        int32_t n_jobs,
                                                        const chert_trace_opts* o) {
   if (!o) return 0;
-  if (is_3d_batch(jobs, n_jobs)) {  // the bucketed plan is the largest
-    chert_trace_opts c = *o;
-    c.bucket_width = 1.0;
-    return chert_trace_batch_workspace_bytes(jobs, n_jobs, &c);
-  }
-  size_t best = 0;
+  // the bucketed frontier plan is the largest frontier plan
+  chert_trace_opts f = *o;
+  f.launch = CHERT_LAUNCH_FRONTIER;
+  f.bucket_width = 1.0;
+  size_t best = chert_trace_batch_workspace_bytes(jobs, n_jobs, &f);
+  if (is_3d_batch(jobs, n_jobs)) return best;
   for (const auto& t : kTuneTiles) {
     chert_trace_opts c = *o;
     c.tile_x = t[0];
     c.tile_z = t[1];
+    c.launch = CHERT_LAUNCH_PER_ROUND;
     const size_t b = chert_trace_batch_workspace_bytes(jobs, n_jobs, &c);
     if (b > best) best = b;
   }
@@ -1608,62 +1609,53 @@ extern "C" int chert_trace_autotune(const chert_trace_job* jobs, int32_t n_jobs,
   // probe: the first source of every job
   std::vector<chert_trace_job> probe(jobs, jobs + n_jobs);
   for (auto& j : probe) j.n_src = j.n_src > 0 ? 1 : 0;
+  std::vector<chert_trace_opts> cands;
+  const bool three_d = is_3d_batch(jobs, n_jobs);
+  const double* bws = three_d ? kTuneBuckets : kTuneBuckets2D;
+  const int n_bws = three_d ? (int)(sizeof(kTuneBuckets) / sizeof(double))
+                            : (int)(sizeof(kTuneBuckets2D) / sizeof(double));
+  for (int q = 0; q < n_bws; ++q) {
+    chert_trace_opts c = *o;
+    c.launch = CHERT_LAUNCH_FRONTIER;
+    c.bucket_width = bws[q];
+    cands.push_back(c);
+  }
+  if (!three_d)
+    for (const auto& t : kTuneTiles)
+      for (int G : kTuneGroups)
+        for (int L : kTuneLaunch) {
+          chert_trace_opts c = *o;
+          c.tile_x = t[0];
+          c.tile_z = t[1];
+          c.push_group = G;
+          c.launch = L;
+          cands.push_back(c);
+        }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(CHERT_ERR_HIP, "event creation failed");
   double best = -1.0;
   chert_trace_opts pick = *o;
   int tried = 0;
-  if (is_3d_batch(jobs, n_jobs)) {
-    for (double bw : kTuneBuckets) {
-      chert_trace_opts c = *o;
-      c.bucket_width = bw;
-      c.stats_host = nullptr;
-      int rc = CHERT_OK;
-      float ms = 0.f;
-      for (int rep = 0; rep < 2 && rc == CHERT_OK; ++rep) {
-        (void)hipEventRecord(e0, s);
-        rc = trace_batch(probe.data(), n_jobs, &c, workspace_dev, workspace_bytes, s);
-        (void)hipEventRecord(e1, s);
-        if (hipEventSynchronize(e1) != hipSuccess) rc = CHERT_ERR_HIP;
-        if (rc == CHERT_OK) (void)hipEventElapsedTime(&ms, e0, e1);
-      }
-      if (rc != CHERT_OK) continue;
-      ++tried;
-      if (best < 0.0 || ms < best) {
-        best = ms;
-        pick = c;
-      }
+  for (chert_trace_opts c : cands) {
+    c.stats_host = nullptr;
+    const size_t need = chert_trace_batch_workspace_bytes(probe.data(), n_jobs, &c);
+    if (need == 0 || need > workspace_bytes) continue;  // shape not valid here
+    int rc = CHERT_OK;
+    float ms = 0.f;
+    for (int rep = 0; rep < 2 && rc == CHERT_OK; ++rep) {  // second run is timed
+      (void)hipEventRecord(e0, s);
+      rc = trace_batch(probe.data(), n_jobs, &c, workspace_dev, workspace_bytes, s);
+      (void)hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess) rc = CHERT_ERR_HIP;
+      if (rc == CHERT_OK) (void)hipEventElapsedTime(&ms, e0, e1);
     }
-  }
-  for (const auto& t : kTuneTiles) {
-    if (is_3d_batch(jobs, n_jobs)) break;
-    for (int G : kTuneGroups)
-      for (int L : kTuneLaunch) {
-        chert_trace_opts c = *o;
-        c.tile_x = t[0];
-        c.tile_z = t[1];
-        c.push_group = G;
-        c.launch = L;
-        c.stats_host = nullptr;
-        const size_t need = chert_trace_batch_workspace_bytes(probe.data(), n_jobs, &c);
-        if (need == 0 || need > workspace_bytes) continue;  // shape not valid here
-        int rc = CHERT_OK;
-        float ms = 0.f;
-        for (int rep = 0; rep < 2 && rc == CHERT_OK; ++rep) {  // second run is timed
-          (void)hipEventRecord(e0, s);
-          rc = trace_batch(probe.data(), n_jobs, &c, workspace_dev, workspace_bytes, s);
-          (void)hipEventRecord(e1, s);
-          if (hipEventSynchronize(e1) != hipSuccess) rc = CHERT_ERR_HIP;
-          if (rc == CHERT_OK) (void)hipEventElapsedTime(&ms, e0, e1);
-        }
-        if (rc != CHERT_OK) continue;
-        ++tried;
-        if (best < 0.0 || ms < best) {
-          best = ms;
-          pick = c;
-        }
-      }
+    if (rc != CHERT_OK) continue;
+    ++tried;
+    if (best < 0.0 || ms < best) {
+      best = ms;
+      pick = c;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

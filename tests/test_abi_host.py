@@ -189,6 +189,45 @@ def test_device_calls_validate_before_launch():
     assert C.chert_trace_workspace_bytes(d, 3, g, 1, o) > 0
 
 
+def test_frontier_launch_validation_and_sizes():
+    """2D batches on the node frontier: same argument checks as the tiles,
+    workspace sized by node counts (lists, stamps) and the weight tables;
+    bad launch values and bucket widths are refused."""
+    d = C.cache_desc()
+    g = C.Grid(2, 3, 10, 10, 1, 5.0, 5.0, 0.0, 1234)
+    of = C.trace_opts(launch=C.LAUNCH_FRONTIER)
+    nf = C.chert_trace_workspace_bytes(d, 3, g, 1, of)
+    nt = C.chert_trace_workspace_bytes(d, 3, g, 1, C.trace_opts())
+    assert nf > 0 and nt > 0 and nf != nt
+    ob = C.trace_opts(launch=C.LAUNCH_FRONTIER, bucket_width=16.0)
+    assert C.chert_trace_workspace_bytes(d, 3, g, 1, ob) > nf  # far piles
+    assert C.chert_trace_workspace_bytes(d, 3, g, 2, of) > nf
+    assert C.chert_trace_workspace_bytes(
+        d, 3, g, 1, C.trace_opts(launch=C.LAUNCH_FRONTIER, bucket_width=-1.0)) == 0
+    assert C.chert_trace_workspace_bytes(d, 3, g, 1, C.trace_opts(launch=7)) == 0
+    gr = C.Grid(2, 9, 10, 10, 1, 5.0, 5.0, 0.0, 1234)
+    assert C.chert_trace_workspace_bytes(d, 3, gr, 1, of) == 0  # radius above 8
+    gp = C.Grid(2, 3, 10, 10, 1, 5.0, 5.0, 0.0, None)  # per node: 100 cache rows
+    assert C.chert_trace_workspace_bytes(d, 100, gp, 1, of) > 0
+    assert C.chert_trace_workspace_bytes(d, 99, gp, 1, of) == 0
+    for bad in ([100], [-1]):
+        with pytest.raises(C.ChertError) as e:
+            C.chert_trace_field(d, _FakeTensor(), 3, g, 0, bad, of, workspace_dev=_FakeTensor(),
+                                stream=0)
+        assert e.value.code == 1
+    with pytest.raises(C.ChertError) as e:  # TSTAR without its inputs
+        C.chert_trace_field(d, _FakeTensor(), 3, g, 0, [0], C.trace_opts(
+            C.OUT_TSTAR, launch=C.LAUNCH_FRONTIER), workspace_dev=_FakeTensor(), stream=0)
+    assert e.value.code == 1
+    dsub = C.cache_desc(subset=C.star_subset(2, 5.0, 5.0))
+    gr5 = C.Grid(2, 5, 10, 10, 1, 5.0, 5.0, 0.0, 1234)  # the subset lacks radius-5 bins
+    with pytest.raises(C.ChertError) as e:
+        C.chert_trace_field(dsub, _Ptr(0x1000), 3, gr5, 0, [0], C.trace_opts(
+            C.OUT_TAU_R, launch=C.LAUNCH_FRONTIER), tau_r=_Ptr(0x2000),
+            workspace_dev=_Ptr(0x3000, n=1 << 40), stream=0)
+    assert e.value.code == 1
+
+
 class _Ptr(_FakeTensor):
     """A fake device pointer value (never dereferenced)."""
     def __init__(self, addr, n=0, shape=(0,)):

@@ -51,7 +51,8 @@ def assert_fields_equal(g, o, s_idx=0):
         assert np.array_equal(a, b), (key, int(np.sum(a != b)))
 
 
-def imported_case(G, model, modes, tile=(0, 0), sources=None, n_sweep=1440, launch=0):
+def imported_case(G, model, modes, tile=(0, 0), sources=None, n_sweep=1440, launch=0,
+                  bucket=0.0):
     cls, f, s = oracle_cache(model, modes, n_sweep)
     Cm = C()
     desc = Cm.cache_desc(n_dirs=model.n_dirs, modes=modes, n_sweep=n_sweep)
@@ -61,7 +62,7 @@ def imported_case(G, model, modes, tile=(0, 0), sources=None, n_sweep=1440, laun
     for mode in modes:
         g = G.trace(cache, desc, K, model.nx, model.nz, model.hx, model.hz, model.radius,
                     model.class_id, mode, sources, tile_x=tile[0], tile_z=tile[1],
-                    launch=launch)
+                    launch=launch, bucket_width=bucket)
         for si, src in enumerate(sources):
             o = O.trace_2d(model.nx, model.nz, model.hx, model.hz, model.class_id,
                            model.radius, f[0, mode], f[1, mode], s[mode], src)
@@ -69,12 +70,13 @@ def imported_case(G, model, modes, tile=(0, 0), sources=None, n_sweep=1440, laun
             assert_fields_equal(g, o, si)
 
 
-@pytest.mark.parametrize("launch", [0, 1])
-def test_imported_cache_small_layered_bitwise(G, launch):
-    """Both launch forms (one launch per round; one persistent launch per
-    phase) reach the oracle's fields bitwise."""
+@pytest.mark.parametrize("launch,bucket", [(0, 0.0), (1, 0.0), (2, 0.0), (2, 8.0)])
+def test_imported_cache_small_layered_bitwise(G, launch, bucket):
+    """Every launch form (one launch per round; one persistent launch per
+    phase; the node frontier with one bucket or near/far buckets) reaches the
+    oracle's fields bitwise."""
     m = W.small_layered()
-    imported_case(G, m, (0, 1, 2), launch=launch)
+    imported_case(G, m, (0, 1, 2), launch=launch, bucket=bucket)
 
 
 @pytest.mark.parametrize("tile", [(8, 8), (16, 4), (32, 16), (64, 16)])
@@ -90,21 +92,24 @@ def test_multiple_sources_one_call(G):
     imported_case(G, m, (0,), sources=srcs)
 
 
-def test_degenerate_grids(G):
-    """One-row and one-column grids, a 1x1 grid, radius 1 and radius 8."""
+@pytest.mark.parametrize("launch", [0, 2])
+def test_degenerate_grids(G, launch):
+    """One-row and one-column grids, a 1x1 grid, radius 1 and radius 8, on
+    the tiles and on the node frontier."""
     for nx, nz, R in [(57, 1, 3), (1, 45, 2), (1, 1, 1), (19, 17, 8), (33, 2, 1)]:
         m = W.small_layered(nx=nx, nz=nz, radius=R, seed=nx + nz)
         m.sources = [min(m.sources[0], nx * nz - 1)]
-        imported_case(G, m, (0,), n_sweep=360)
+        imported_case(G, m, (0,), n_sweep=360, launch=launch)
 
 
-def test_fluid_region_blocks_shear(G):
+@pytest.mark.parametrize("launch", [0, 2])
+def test_fluid_region_blocks_shear(G, launch):
     """A class without shear stiffness: shear-mode edges into it are
     impassable (tau = inf, pred = -1), qP passes."""
     m = W.small_layered(nx=30, nz=20, radius=3, seed=11)
     from workloads import Layer
     m.layers[0] = Layer(1500.0, 0.0, 1000.0, 0.0, 0.0, 0.0, 0.0, 1000.0, 1000.0)
-    imported_case(G, m, (0, 1), n_sweep=360)
+    imported_case(G, m, (0, 1), n_sweep=360, launch=launch)
 
 
 def test_end_to_end_config1(G):
@@ -126,8 +131,10 @@ def test_end_to_end_config1(G):
             assert rel.max() <= 1e-9, (key, rel.max())
 
 
-def test_end_to_end_config2_full_size(G):
-    """Config 2 (401 x 201, radius 5, 5 classes, 3 modes) end to end."""
+@pytest.mark.parametrize("launch", [0, 2])
+def test_end_to_end_config2_full_size(G, launch):
+    """Config 2 (401 x 201, radius 5, 5 classes, 3 modes) end to end, on the
+    tiles and on the node frontier."""
     m = W.config2()
     Cm = C()
     desc = Cm.cache_desc(n_dirs=360, modes=m.modes)
@@ -135,7 +142,7 @@ def test_end_to_end_config2_full_size(G):
     cls, f, s = oracle_cache(m, m.modes)
     for mode in m.modes:
         g = G.trace(cache, desc, len(m.layers), m.nx, m.nz, m.hx, m.hz, m.radius, m.class_id,
-                    mode, m.sources)
+                    mode, m.sources, launch=launch)
         o = O.trace_2d(m.nx, m.nz, m.hx, m.hz, m.class_id, m.radius, f[0, mode], f[1, mode],
                        s[mode], m.sources[0])
         for key in ("tauR", "tauI", "tstar"):
@@ -147,7 +154,8 @@ def test_end_to_end_config2_full_size(G):
             assert rel.max() <= 1e-9, (key, rel.max())
 
 
-def test_invalid_class_id_reported(G):
+@pytest.mark.parametrize("launch", [0, 2])
+def test_invalid_class_id_reported(G, launch):
     m = W.small_layered(nx=20, nz=10, radius=2, seed=1)
     cls, f, s = oracle_cache(m, (0,), n_sweep=360)
     Cm = C()
@@ -156,7 +164,8 @@ def test_invalid_class_id_reported(G):
     cid = m.class_id.copy()
     cid[3, 4] = 99
     with pytest.raises(Cm.ChertError) as e:
-        G.trace(cache, desc, cls.shape[0], m.nx, m.nz, m.hx, m.hz, m.radius, cid, 0, m.sources)
+        G.trace(cache, desc, cls.shape[0], m.nx, m.nz, m.hx, m.hz, m.radius, cid, 0, m.sources,
+                launch=launch)
     assert e.value.code == 1
 
 
@@ -201,20 +210,23 @@ def check_batch(jobs):
             assert_fields_equal(g, o, si)
 
 
-@pytest.mark.parametrize("launch", [0, 1])
-def test_batch_uneven_grids_modes_sources_bitwise(G, launch):
+@pytest.mark.parametrize("launch,bucket", [(0, 0.0), (1, 0.0), (2, 0.0), (2, 16.0)])
+def test_batch_uneven_grids_modes_sources_bitwise(G, launch, bucket):
     """chert_trace_batch over uneven grids, modes and sources: every field
-    bitwise equal to the oracle, in both launch forms."""
+    bitwise equal to the oracle, in every launch form."""
     Cm = C()
     b, jobs, keep = uneven_batch(G)
     stats = Cm.TraceStats()
-    opts = Cm.trace_opts(Cm.OUT_ALL, launch=launch, stats=stats)
+    opts = Cm.trace_opts(Cm.OUT_ALL, launch=launch, stats=stats, bucket_width=bucket)
     ws = torch.empty(Cm.chert_trace_batch_workspace_bytes(b, opts), dtype=torch.uint8,
                      device=G.DEV)
     Cm.chert_trace_batch(b, opts, ws)
     torch.cuda.synchronize()
-    print("launch", launch, stats.as_dict())
-    assert min(stats.rounds) > 0
+    print("launch", launch, "bucket", bucket, stats.as_dict())
+    if launch == Cm.LAUNCH_FRONTIER:
+        assert stats.rounds[0] > 0 and stats.rounds[1] > 0
+    else:
+        assert min(stats.rounds) > 0
     check_batch(jobs)
 
 
@@ -264,9 +276,13 @@ def test_autotuned_options_give_identical_fields(G):
     ws = torch.empty(Cm.chert_trace_autotune_workspace_bytes(b, opts), dtype=torch.uint8,
                      device=G.DEV)
     ms = Cm.chert_trace_autotune(b, opts, ws)
-    print("autotuned", opts.tile_x, opts.tile_z, opts.push_group, opts.launch, ms)
-    assert ms > 0 and opts.push_group in (1, 2, 4) and opts.launch in (0, 1)
-    assert opts.tile_x * opts.tile_z <= 1024
+    print("autotuned", opts.tile_x, opts.tile_z, opts.push_group, opts.launch, opts.bucket_width,
+          ms)
+    assert ms > 0 and opts.launch in (0, 1, 2)
+    if opts.launch == Cm.LAUNCH_FRONTIER:
+        assert opts.bucket_width in (0.0, 16.0, 64.0)
+    else:
+        assert opts.push_group in (1, 2, 4) and opts.tile_x * opts.tile_z <= 1024
     for j in jobs:
         for t in j[5].values():
             t.fill_(-3)
@@ -275,9 +291,11 @@ def test_autotuned_options_give_identical_fields(G):
     check_batch(jobs)
 
 
-def test_per_node_trace_bitwise(G):
+@pytest.mark.parametrize("launch,bucket", [(0, 0.0), (2, 0.0), (2, 16.0)])
+def test_per_node_trace_bitwise(G, launch, bucket):
     """Per-node cache (no class map): GPU traveltimes and predecessors on an
-    imported oracle cache are bitwise the oracle's."""
+    imported oracle cache are bitwise the oracle's, on the tiles and on the
+    node frontier."""
     import torch
     Cm = C()
     m = W.complex_2d(nx=45, nz=33, h=10.0, water_m=60.0, n_layers=8, n_faults=2, seed=5,
@@ -297,7 +315,7 @@ def test_per_node_trace_bitwise(G):
                    pred_p=torch.empty((1, n), dtype=torch.int32, device=G.DEV),
                    pred_a=torch.empty((1, n), dtype=torch.int32, device=G.DEV))
         grid = Cm.make_grid(m.nx, m.nz, m.hx, m.hz, m.radius, None)
-        opts = Cm.trace_opts(Cm.OUT_ALL)
+        opts = Cm.trace_opts(Cm.OUT_ALL, launch=launch, bucket_width=bucket)
         ws = torch.empty(Cm.chert_trace_workspace_bytes(desc, N, grid, 1, opts),
                          dtype=torch.uint8, device=G.DEV)
         Cm.chert_trace_field(desc, cache, N, grid, mode, m.sources, opts, workspace_dev=ws, **out)
