@@ -262,11 +262,16 @@ typedef struct chert_trace_opts {
   int32_t push_group; /* star offsets per push work item: 1, 2 or 4 (0 = 2) */
   int32_t launch;     /* CHERT_LAUNCH_PER_ROUND (0), _PERSISTENT (1) or
                          _FRONTIER (2)                                     */
-  double bucket_width;/* frontier iteration: near/far bucket width in units
-                         of the batch's smallest positive edge weight of the
-                         field; 0 = one bucket (every improvement is relaxed
-                         next iteration).  Ignored by the tile launches.
-                         Must be >= 0.                                     */
+  double bucket_width;/* ordering width in units of the batch's smallest
+                         positive edge weight of the field (0 = none; must
+                         be >= 0).  Frontier iteration: near/far buckets,
+                         an improvement at or above the problem's far
+                         minimum + width waits.  Tiles: a tile woken with
+                         key k (smallest changed border value: tau, t*, or
+                         the hop count with the width in hops) is visited
+                         only once k <= its problem's smallest pending key
+                         + width; otherwise it stays active for a later
+                         round.  The fields do not depend on it.          */
   chert_trace_stats *stats_host; /* nullable: filled when the call returns */
 } chert_trace_opts;
 
@@ -328,7 +333,8 @@ int chert_trace_batch(const chert_trace_job *jobs, int32_t n_jobs,
  * with bucket widths 0 (one bucket), 4, 16, 32, 64, 128, 256 (units of the
  * smallest edge weight); in 2D the frontier with widths 0, 16, 64 and the
  * tiles 32x32, 64x16, 16x64, 32x16, 16x32, 128x8 with push groups 1, 2, 4,
- * per-round and persistent launch.  Each is timed (HIP events,
+ * per-round and persistent launch, then, if tiles win, their ordering width
+ * 16, 64 or 256 on the fastest shape.  Each is timed (HIP events,
  * second of two runs) on a probe batch made of the first source of every
  * job; the fastest is written into o->tile_x, tile_z, push_group, launch and
  * bucket_width (other fields are kept) and its probe time into *best_ms
@@ -478,7 +484,8 @@ int chert_surrogate_infer(const void *blob_dev, const float *x_dev, int64_t n,
  * the windowed plain search), [4] Newton not converged, [5] slope of the
  * ray-angle map too small, [6] theta_I not the root nearest 0, [7] residual
  * or entry rejected, [8] sweep samples evaluated by windowed searches,
- * [9] jobs whose windowed search failed its guard. */
+ * [9] jobs whose windowed search failed its guard or needed more than 512
+ * sweep samples. */
 enum { CHERT_WARM_NSTATS = 10 };
 
 /* Scratch needed by chert_build_cache_surrogate. */

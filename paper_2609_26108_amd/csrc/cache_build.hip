@@ -223,15 +223,42 @@ __device__ __forceinline__ void store_invalid(const SolveArgs& a, int64_t base, 
 
 constexpr int kMaxBr = 6;  // brackets kept per lane for the lockstep refinement
 
+// Sweep tables as solve_dir reads them: (theta_I, ray angle) of sample j,
+// NaN angle where the sample has no root.  A full table holds every sample;
+// a windowed one holds the marked samples in ascending order (slot q is
+// sample idx[q], pos[j] is the slot of sample j or -1) and reads every other
+// sample as NaN.  count()/sample(q) enumerate the samples that can open a
+// bracket, in ascending order.
+struct FullTable {
+  const double2* t;
+  int n;
+  __device__ __forceinline__ double2 at(int j) const { return t[j]; }
+  __device__ __forceinline__ int count() const { return n; }
+  __device__ __forceinline__ int sample(int q) const { return q; }
+};
+struct WindowTable {
+  const int16_t* pos;
+  const double2* ent;
+  const int16_t* idx;
+  int nl;
+  __device__ __forceinline__ double2 at(int j) const {
+    const int p = pos[j];
+    return p < 0 ? make_double2(0.0, NAN) : ent[p];
+  }
+  __device__ __forceinline__ int count() const { return nl; }
+  __device__ __forceinline__ int sample(int q) const { return idx[q]; }
+};
+
 // Refine the bracket starting at sweep sample j and fold the root into the
 // running first-arrival choice (largest ray velocity; ties to the smaller
 // |theta_R - psi*|).
+template <class T>
 __device__ __forceinline__ void refine_bracket(const SolveArgs& a, const Medium& m, int mode,
-                                               const double2* tab, int j, double psi_star,
-                                               bool el, bool* found, bool* ill, Entry* best) {
+                                               const T& tab, int j, double psi_star, bool el,
+                                               bool* found, bool* ill, Entry* best) {
   const double dth = kTwoPi / a.n_sweep;
-  double2 sa = tab[j];
-  double2 sb = tab[j + 1 == a.n_sweep ? 0 : j + 1];
+  double2 sa = tab.at(j);
+  double2 sb = tab.at(j + 1 == a.n_sweep ? 0 : j + 1);
   double fa = wrap_pi(sa.y - psi_star);
   double fb = wrap_pi(sb.y - psi_star);
   double ta = (j + 0.5) * dth;
@@ -262,9 +289,10 @@ __device__ __forceinline__ void refine_bracket(const SolveArgs& a, const Medium&
   }
 }
 
-__device__ __forceinline__ bool is_bracket(const double2* tab, int j, int n, double psi_star) {
-  double2 sa = tab[j];
-  double2 sb = tab[j + 1 == n ? 0 : j + 1];
+template <class T>
+__device__ __forceinline__ bool is_bracket(const T& tab, int j, int n, double psi_star) {
+  double2 sa = tab.at(j);
+  double2 sb = tab.at(j + 1 == n ? 0 : j + 1);
   if (isnan(sa.y) || isnan(sb.y)) return false;
   double fa = wrap_pi(sa.y - psi_star);
   double fb = wrap_pi(sb.y - psi_star);
@@ -275,13 +303,15 @@ __device__ __forceinline__ bool is_bracket(const double2* tab, int j, int n, dou
 // Solve target direction d for one (class, mode) from its sweep table in
 // LDS.  Lanes of a wavefront run it in step (brackets first, then the
 // refinements together); `br` is this lane's kMaxBr bracket slots in LDS.
+template <class T>
 __device__ __forceinline__ int32_t solve_dir(const SolveArgs& a, const Medium& m, int mode,
-                                             const double2* tab, double psi_star, int* br,
+                                             const T& tab, double psi_star, int* br,
                                              Entry* best) {
   const bool el = theta_i_zero(m, mode);
   // phase 1: every sign change of the ray-direction miss over the sweep
   int nbr = 0;
-  for (int j = 0; j < a.n_sweep; ++j) {
+  for (int q = 0; q < tab.count(); ++q) {
+    const int j = tab.sample(q);
     if (!is_bracket(tab, j, a.n_sweep, psi_star)) continue;
     if (nbr < kMaxBr) br[nbr] = j;
     ++nbr;
@@ -295,7 +325,8 @@ __device__ __forceinline__ int32_t solve_dir(const SolveArgs& a, const Medium& m
   // rare: more brackets than slots; refine the rest in scan order
   if (nbr > kMaxBr) {
     int seen = 0;
-    for (int j = 0; j < a.n_sweep; ++j) {
+    for (int q = 0; q < tab.count(); ++q) {
+      const int j = tab.sample(q);
       if (!is_bracket(tab, j, a.n_sweep, psi_star)) continue;
       if (seen++ < kMaxBr) continue;
       refine_bracket(a, m, mode, tab, j, psi_star, el, &found, &ill, best);
@@ -380,7 +411,8 @@ __global__ void __launch_bounds__(64) k_solve(SolveArgs a) {
     const int64_t stride = 3 * a.n_classes * (int64_t)a.n_cols;
     if (!st) {
       const Medium m = load_medium(c);
-      st = solve_dir(a, m, mode, tab, polar_to_axis(f, c), s_br + threadIdx.x * kMaxBr, &best);
+      st = solve_dir(a, m, mode, FullTable{tab, a.n_sweep}, polar_to_axis(f, c),
+                     s_br + threadIdx.x * kMaxBr, &best);
     }
     store_single(a, row + sidx, stride, best, f, st);
     return;
@@ -392,7 +424,8 @@ __global__ void __launch_bounds__(64) k_solve(SolveArgs a) {
     return;
   }
   const Medium m = load_medium(c);
-  st = solve_dir(a, m, mode, tab, dir_psi(a, d, m.tilt), s_br + threadIdx.x * kMaxBr, &best);
+  st = solve_dir(a, m, mode, FullTable{tab, a.n_sweep}, dir_psi(a, d, m.tilt),
+                 s_br + threadIdx.x * kMaxBr, &best);
   store_pair(a, row, col, pcol, best, m.tilt, st);
 }
 
@@ -440,7 +473,7 @@ __global__ void __launch_bounds__(kNodeThreads) k_build_fused(SolveArgs a, const
       int d, col, pcol;
       dir_cols(a, sidx, &d, &col, &pcol);
       Entry best{};
-      const int32_t st = solve_dir(a, m, mode, tab, dir_psi(a, d, m.tilt),
+      const int32_t st = solve_dir(a, m, mode, FullTable{tab, a.n_sweep}, dir_psi(a, d, m.tilt),
                                    s_br + threadIdx.x * kMaxBr, &best);
       store_pair(a, row, col, pcol, best, m.tilt, st);
     }
@@ -467,32 +500,32 @@ struct WarmArgs {
   float2* pred;                 // [jobs][n_solve] (theta_R - psi, theta_I)
   int32_t* fb_list;             // jobs for the plain path
   int32_t* fb_len;
+  int32_t* win_list;            // jobs with directions near a fold (k_warm_window)
+  int32_t* win_len;
   unsigned long long* stats;    // CHERT_WARM_NSTATS counters
   double resid_tol;
 };
 
-// surrogate predictions for every (job, solved direction): 32 per workgroup
+// surrogate predictions for every (job, solved direction): kInferRows per
+// workgroup
 __global__ void __launch_bounds__(mlp::kThreads) k_warm_predict(WarmArgs w, int64_t n_rows) {
   __shared__ mlp::InferTile t;
   const SolveArgs& a = w.so;
   const mlp::Net n = mlp::net_of(w.blob);
-  const int64_t base = (int64_t)blockIdx.x * mlp::kRows;
-  __shared__ float s_f[mlp::kRows][mlp::kIn];
-  if (threadIdx.x < mlp::kRows) {
-    const int64_t e = base + threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * mlp::kInferRows;
+  for (int r = threadIdx.x; r < mlp::kInferRows; r += blockDim.x) {
+    const int64_t e = base + r;
+    float f[mlp::kIn] = {};
     if (e < n_rows) {
       const int64_t job = e / a.n_solve;
       const int sidx = (int)(e % a.n_solve);
       const chert_class c = a.classes[job % a.n_classes];
       int d, col, pcol;
       dir_cols(a, sidx, &d, &col, &pcol);
-      mlp::features(c, a.modes[job / a.n_classes], dir_psi(a, d, c.tilt), s_f[threadIdx.x]);
-    } else {
-      for (int i = 0; i < mlp::kIn; ++i) s_f[threadIdx.x][i] = NAN;
+      mlp::features(c, a.modes[job / a.n_classes], dir_psi(a, d, c.tilt), f);
     }
+    mlp::stage_row(n, t.x, r, f, e >= n_rows);
   }
-  __syncthreads();
-  mlp::stage_x<false>(n, t.x, nullptr, [&](int r, int i) -> float { return s_f[r][i]; });
   __syncthreads();
   mlp::forward_infer(n, t, [&](int r, int col, float v) {
     if (col < 2 && base + r < n_rows) (&w.pred[base + r].x)[col] = v;
@@ -578,7 +611,6 @@ __device__ __forceinline__ int fold_bin(double psi) {
   return b < 0 ? b + kFoldBins : b;
 }
 
-// one wavefront per (mode, class) job
 // sweep samples whose theta_R the elastic map sends within kFoldMargin of
 // psi_star (either half of the circle), plus one sample on each side
 __device__ __forceinline__ void mark_window(const SolveArgs& a, const double* psi, double psi_star,
@@ -606,60 +638,22 @@ __device__ __forceinline__ void mark_window(const SolveArgs& a, const double* ps
   }
 }
 
-__global__ void __launch_bounds__(64) k_warm_solve(WarmArgs w) {
-  extern __shared__ double2 tab[];  // windowed sweep table [n_sweep], then the sample list
-  __shared__ double s_psi[kProxyN];
-  __shared__ uint32_t s_fold[kFoldWords];
-  __shared__ uint32_t s_cnt[CHERT_WARM_NSTATS];
-  __shared__ uint32_t s_mask[kMaxSweep / 32];
-  __shared__ int16_t s_flag[kMaxSubset / 2];
-  __shared__ int s_br[64 * kMaxBr];
-  __shared__ int s_all, s_nflag, s_nlist, s_bad;
-
-  const SolveArgs& a = w.so;
-  const int64_t job = blockIdx.x;
+// Elastic stand-in of the ray-angle map psi(theta_R) on [0, pi) (the other
+// half is its centrosymmetric image): folds and near-folds within the margin
+// mark ray-angle bins where the map may have several branches.  All 64 lanes;
+// s_fold and *s_all must be cleared (and a barrier passed) before the call;
+// ends with a barrier.
+__device__ __forceinline__ void proxy_folds(const Medium& me, int mode, int kernel, double* s_psi,
+                                            uint32_t* s_fold, int* s_all) {
   const int lane = threadIdx.x;
-  const int64_t k = job % a.n_classes;
-  const int mode = a.modes[job / a.n_classes];
-  const chert_class c = a.classes[k];
-  const int64_t row = ((int64_t)mode * a.n_classes + k) * a.n_cols;
-  int16_t* s_list = reinterpret_cast<int16_t*>(tab + a.n_sweep);
-  if (lane < CHERT_WARM_NSTATS) s_cnt[lane] = 0;
-  if (lane < kFoldWords) s_fold[lane] = 0;
-  if (lane == 0) {
-    s_all = 0;
-    s_nflag = 0;
-    s_bad = 0;
-  }
-  const int32_t blocked = class_block(c, mode);
-  if (blocked) {
-    Entry none{};
-    none.V = NAN;
-    for (int sidx = lane; sidx < a.n_solve; sidx += 64) {
-      int d, col, pcol;
-      dir_cols(a, sidx, &d, &col, &pcol);
-      store_pair(a, row, col, pcol, none, 0.0, blocked);
-    }
-    if (lane == 0) atomicAdd(&w.stats[0], 1ull);
-    return;  // block-uniform
-  }
-  const Medium m = load_medium(c);
-  const bool el = theta_i_zero(m, mode);
-
-  // elastic stand-in of the ray-angle map psi(theta_R) on [0, pi) (the other
-  // half is its centrosymmetric image); folds and near-folds within the
-  // margin mark ray-angle bins where the map may have several branches
-  Medium me = m;
-  me.a11.im = me.a13.im = me.a33.im = me.a44.im = me.a66.im = 0.0;
-  me.elastic_ps = me.elastic_sh = true;
   for (int j = lane; j < kProxyN; j += 64)
-    s_psi[j] = ray_angle(energy_velocity(me, mode, a.kernel, (j + 0.5) * (kPi / kProxyN), 0.0));
+    s_psi[j] = ray_angle(energy_velocity(me, mode, kernel, (j + 0.5) * (kPi / kProxyN), 0.0));
   __syncthreads();
   for (int j = lane; j < kProxyN; j += 64) {
     const double pa = s_psi[j];
     const double pb = j + 1 < kProxyN ? s_psi[j + 1] : s_psi[0] + kPi;
     if (!isfinite(pa) || !isfinite(pb)) {
-      s_all = 1;
+      *s_all = 1;
       continue;
     }
     const double dp = wrap_pi(pb - pa);
@@ -676,6 +670,55 @@ __global__ void __launch_bounds__(64) k_warm_solve(WarmArgs w) {
     }
   }
   __syncthreads();
+}
+
+__device__ __forceinline__ Medium elastic_of(const Medium& m) {
+  Medium me = m;
+  me.a11.im = me.a13.im = me.a33.im = me.a44.im = me.a66.im = 0.0;
+  me.elastic_ps = me.elastic_sh = true;
+  return me;
+}
+
+// One wavefront per (mode, class) job: every direction away from a fold is
+// polished from its prediction.  A job with a rejected direction goes to the
+// plain path (fb_list); a job whose other directions all passed and that has
+// directions near a fold goes to k_warm_window (win_list).  Small static LDS
+// only, so occupancy is set by registers.
+__global__ void __launch_bounds__(64) k_warm_solve(WarmArgs w) {
+  __shared__ double s_psi[kProxyN];
+  __shared__ uint32_t s_fold[kFoldWords];
+  __shared__ uint32_t s_cnt[CHERT_WARM_NSTATS];
+  __shared__ int s_all, s_nflag;
+
+  const SolveArgs& a = w.so;
+  const int64_t job = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t k = job % a.n_classes;
+  const int mode = a.modes[job / a.n_classes];
+  const chert_class c = a.classes[k];
+  const int64_t row = ((int64_t)mode * a.n_classes + k) * a.n_cols;
+  if (lane < CHERT_WARM_NSTATS) s_cnt[lane] = 0;
+  if (lane < kFoldWords) s_fold[lane] = 0;
+  if (lane == 0) {
+    s_all = 0;
+    s_nflag = 0;
+  }
+  const int32_t blocked = class_block(c, mode);
+  if (blocked) {
+    Entry none{};
+    none.V = NAN;
+    for (int sidx = lane; sidx < a.n_solve; sidx += 64) {
+      int d, col, pcol;
+      dir_cols(a, sidx, &d, &col, &pcol);
+      store_pair(a, row, col, pcol, none, 0.0, blocked);
+    }
+    if (lane == 0) atomicAdd(&w.stats[0], 1ull);
+    return;  // block-uniform
+  }
+  const Medium m = load_medium(c);
+  const bool el = theta_i_zero(m, mode);
+  __syncthreads();
+  proxy_folds(elastic_of(m), mode, a.kernel, s_psi, s_fold, &s_all);
 
   bool reject = false;
   for (int sidx = lane; sidx < a.n_solve; sidx += 64) {
@@ -688,9 +731,9 @@ __global__ void __launch_bounds__(64) k_warm_solve(WarmArgs w) {
       reject = true;
       continue;
     }
-    if ((s_fold[fb >> 5] >> (fb & 31)) & 1u) {  // near a fold: windowed plain search below
+    if ((s_fold[fb >> 5] >> (fb & 31)) & 1u) {  // near a fold: k_warm_window
       atomicAdd(&s_cnt[3], 1u);
-      s_flag[atomicAdd(&s_nflag, 1)] = (int16_t)sidx;
+      atomicAdd(&s_nflag, 1);
       continue;
     }
     const float2 p = w.pred[job * a.n_solve + sidx];
@@ -727,42 +770,113 @@ __global__ void __launch_bounds__(64) k_warm_solve(WarmArgs w) {
     }
     store_pair(a, row, col, pcol, e, m.tilt, CHERT_ST_OK);
   }
-  bool any = __any(reject);
+  const bool any = __any(reject);
   __syncthreads();
+  if (lane == 0) {
+    s_cnt[0] = 1;
+    if (any) {
+      s_cnt[1] = 1;
+      w.fb_list[atomicAdd(w.fb_len, 1)] = (int32_t)job;
+    } else if (s_nflag > 0) {
+      w.win_list[atomicAdd(w.win_len, 1)] = (int32_t)job;
+    }
+  }
+  __syncthreads();
+  if (lane < CHERT_WARM_NSTATS && s_cnt[lane]) atomicAdd(&w.stats[lane], (unsigned long long)s_cnt[lane]);
+}
 
-  // Directions near a fold: the plain sweep-and-bracket search, evaluated
-  // only at the sweep samples the elastic map places within kFoldMargin of
-  // the target ray angle.  Samples left out stay NaN and so never bracket;
-  // the search is the plain one wherever the viscoelastic map stays within
-  // kFoldMargin of the elastic one, which is checked on every evaluated
-  // sample (half the margin; otherwise the job goes to the plain path).
-  const int nflag = s_nflag;
-  if (!any && nflag > 0) {
-    for (int i = lane; i < a.n_sweep; i += 64) tab[i] = make_double2(0.0, NAN);
-    for (int i = lane; i < (a.n_sweep + 31) / 32; i += 64) s_mask[i] = 0u;
+// Directions near a fold, for the jobs k_warm_solve listed: the plain
+// sweep-and-bracket search, evaluated only at the sweep samples the elastic
+// map places within kFoldMargin of the target ray angle.  Samples left out
+// read as NaN and so never bracket; the search is the plain one wherever the
+// viscoelastic map stays within kFoldMargin of the elastic one, which is
+// checked on every evaluated sample (half the margin; otherwise, or beyond
+// kWinCap samples, the job goes to the plain path).  One wavefront per
+// listed job, grid-strided; the marked samples are kept compact in LDS.
+constexpr int kWinCap = 512;
+__global__ void __launch_bounds__(64) k_warm_window(WarmArgs w) {
+  extern __shared__ double2 s_ent[];  // [kWinCap] (theta_I, psi); then idx, pos
+  int16_t* s_idx = reinterpret_cast<int16_t*>(s_ent + kWinCap);  // [kWinCap]
+  __shared__ double s_psi[kProxyN];
+  __shared__ uint32_t s_fold[kFoldWords];
+  __shared__ uint32_t s_mask[kMaxSweep / 32];
+  __shared__ int16_t s_flag[kMaxSubset / 2];
+  __shared__ int s_br[64 * kMaxBr];
+  __shared__ int s_all, s_nflag, s_bad;
+
+  const SolveArgs& a = w.so;
+  const int lane = threadIdx.x;
+  int16_t* s_pos = s_idx + kWinCap;  // [n_sweep]
+  const int n_words = (a.n_sweep + 31) / 32;
+  const int n_list = *w.win_len;
+  unsigned long long samples = 0, guard = 0;
+  for (int q = blockIdx.x; q < n_list; q += gridDim.x) {
+    const int64_t job = w.win_list[q];
+    const int64_t k = job % a.n_classes;
+    const int mode = a.modes[job / a.n_classes];
+    const chert_class c = a.classes[k];
+    const int64_t row = ((int64_t)mode * a.n_classes + k) * a.n_cols;
+    const Medium m = load_medium(c);
+    const Medium me = elastic_of(m);
+    __syncthreads();  // the previous job is done with the shared arrays
+    if (lane < kFoldWords) s_fold[lane] = 0;
+    if (lane == 0) {
+      s_all = 0;
+      s_nflag = 0;
+      s_bad = 0;
+    }
+    for (int i = lane; i < a.n_sweep; i += 64) s_pos[i] = -1;
+    for (int i = lane; i < n_words; i += 64) s_mask[i] = 0u;
     __syncthreads();
+    proxy_folds(me, mode, a.kernel, s_psi, s_fold, &s_all);
+    for (int sidx = lane; sidx < a.n_solve; sidx += 64) {
+      int d, col, pcol;
+      dir_cols(a, sidx, &d, &col, &pcol);
+      const int fb = fold_bin(dir_psi(a, d, m.tilt));
+      if ((s_fold[fb >> 5] >> (fb & 31)) & 1u) s_flag[atomicAdd(&s_nflag, 1)] = (int16_t)sidx;
+    }
+    __syncthreads();
+    const int nflag = s_nflag;
     for (int f = 0; f < nflag; ++f) {
       int d, col, pcol;
       dir_cols(a, s_flag[f], &d, &col, &pcol);
       mark_window(a, s_psi, dir_psi(a, d, m.tilt), s_mask);
     }
     __syncthreads();
-    if (lane == 0) {
-      int nl = 0;
-      for (int wd = 0; wd < (a.n_sweep + 31) / 32; ++wd) {
-        uint32_t bits = s_mask[wd];
-        while (bits) {
-          const int b = __builtin_ctz(bits);
-          bits &= bits - 1u;
-          s_list[nl++] = (int16_t)(wd * 32 + b);
-        }
+    // marked samples in ascending order: one mask word per lane, prefix sum
+    // of the word populations across the wavefront
+    int nl = 0;
+    for (int base = 0; base < n_words; base += 64) {
+      const int wd = base + lane;
+      uint32_t bits = wd < n_words ? s_mask[wd] : 0u;
+      const int cnt = __popc(bits);
+      int incl = cnt;
+      for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off);
+        if (lane >= off) incl += v;
       }
-      s_nlist = nl;
+      int slot = nl + incl - cnt;
+      while (bits) {
+        const int b = __builtin_ctz(bits);
+        bits &= bits - 1u;
+        if (slot < kWinCap) {
+          s_idx[slot] = (int16_t)(wd * 32 + b);
+          s_pos[wd * 32 + b] = (int16_t)slot;
+        }
+        ++slot;
+      }
+      nl += __shfl(incl, 63);
+    }
+    if (nl > kWinCap) {  // wavefront-uniform
+      if (lane == 0) {
+        ++guard;
+        w.fb_list[atomicAdd(w.fb_len, 1)] = (int32_t)job;
+      }
+      continue;
     }
     __syncthreads();
-    const int nl = s_nlist;
-    for (int q = lane; q < nl; q += 64) {
-      const int i = s_list[q];
+    for (int t = lane; t < nl; t += 64) {
+      const int i = s_idx[t];
       const double thR = (i + 0.5) * (kTwoPi / a.n_sweep);
       double thI;
       double2 out = make_double2(0.0, NAN);
@@ -772,14 +886,17 @@ __global__ void __launch_bounds__(64) k_warm_solve(WarmArgs w) {
         const double pe = ray_angle(energy_velocity(me, mode, a.kernel, thR, 0.0));
         if (!(fabs(wrap_pi(psi - pe)) <= 0.5 * kFoldMargin)) s_bad = 1;
       }
-      tab[i] = out;
+      s_ent[t] = out;
     }
-    if (lane == 0) atomicAdd(&s_cnt[8], (uint32_t)nl);
+    samples += (unsigned long long)nl;
     __syncthreads();
     if (s_bad) {
-      any = true;
-      if (lane == 0) s_cnt[9] = 1;
+      if (lane == 0) {
+        ++guard;
+        w.fb_list[atomicAdd(w.fb_len, 1)] = (int32_t)job;
+      }
     } else {
+      const WindowTable tab{s_pos, s_ent, s_idx, nl};
       for (int f = lane; f < nflag; f += 64) {
         int d, col, pcol;
         dir_cols(a, s_flag[f], &d, &col, &pcol);
@@ -790,20 +907,16 @@ __global__ void __launch_bounds__(64) k_warm_solve(WarmArgs w) {
       }
     }
   }
-  if (lane == 0) {
-    s_cnt[0] = 1;
-    if (any) {
-      s_cnt[1] = 1;
-      const int32_t pos = atomicAdd(w.fb_len, 1);
-      w.fb_list[pos] = (int32_t)job;
-    }
+  if (lane == 0 && samples) atomicAdd(&w.stats[8], samples);
+  if (lane == 0 && guard) {
+    atomicAdd(&w.stats[9], guard);
+    atomicAdd(&w.stats[1], guard);
   }
-  __syncthreads();
-  if (lane < CHERT_WARM_NSTATS && s_cnt[lane]) atomicAdd(&w.stats[lane], (unsigned long long)s_cnt[lane]);
 }
 
-__global__ void k_warm_zero(int32_t* fb_len, unsigned long long* stats) {
+__global__ void k_warm_zero(int32_t* fb_len, int32_t* win_len, unsigned long long* stats) {
   if (threadIdx.x == 0) *fb_len = 0;
+  if (threadIdx.x == 1) *win_len = 0;
   if (threadIdx.x < CHERT_WARM_NSTATS) stats[threadIdx.x] = 0ull;
 }
 
@@ -949,8 +1062,8 @@ extern "C" int chert_build_cache(const chert_cache_desc* d, const chert_class* c
   return launch_status();
 }
 
-// workspace of the surrogate-started build: predictions, fallback job list,
-// its length and the internal counters
+// workspace of the surrogate-started build: predictions, the fallback and
+// fold-window job lists, their lengths and the internal counters
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 extern "C" size_t chert_build_cache_surrogate_workspace_bytes(const chert_cache_desc* d,
@@ -959,7 +1072,7 @@ extern "C" size_t chert_build_cache_surrogate_workspace_bytes(const chert_cache_
   if (!d || n_classes <= 0 || chert_cache_layout_of(d, n_classes, &lay) != CHERT_OK) return 0;
   const SolveArgs so = solve_args(d, nullptr, n_classes, nullptr, lay, nullptr);
   const size_t jobs = (size_t)n_jobs_of(d, n_classes);
-  return al256(jobs * so.n_solve * sizeof(float2)) + al256(jobs * sizeof(int32_t)) + 256;
+  return al256(jobs * so.n_solve * sizeof(float2)) + 2 * al256(jobs * sizeof(int32_t)) + 256;
 }
 
 extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
@@ -991,21 +1104,26 @@ extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
   w.blob = blob_dev;
   w.pred = (float2*)ws;
   w.fb_list = (int32_t*)(ws + al256(rows * sizeof(float2)));
-  w.fb_len = (int32_t*)(ws + al256(rows * sizeof(float2)) + al256(jobs * sizeof(int32_t)));
+  w.win_list = (int32_t*)(ws + al256(rows * sizeof(float2)) + al256(jobs * sizeof(int32_t)));
+  w.fb_len = (int32_t*)(ws + al256(rows * sizeof(float2)) + 2 * al256(jobs * sizeof(int32_t)));
+  w.win_len = w.fb_len + 1;
   w.stats = stats_dev ? (unsigned long long*)stats_dev : (unsigned long long*)(w.fb_len + 16);
   w.resid_tol = resid_tol > 0.0 ? resid_tol : 1e-11;
 
   CHERT_LAUNCH("k_write_header", k_write_header, dim3(1), dim3(64), 0, s, cache, d->dim,
                d->n_dirs, d->mode_mask, d->kernel, d->n_sweep, d->n_subset, n_classes);
-  CHERT_LAUNCH("k_warm_zero", k_warm_zero, dim3(1), dim3(64), 0, s, w.fb_len, w.stats);
+  CHERT_LAUNCH("k_warm_zero", k_warm_zero, dim3(1), dim3(64), 0, s, w.fb_len, w.win_len,
+               w.stats);
   if (jobs > 0 && rows > 0) {
-    const int64_t blocks = (rows + mlp::kRows - 1) / mlp::kRows;
+    const int64_t blocks = (rows + mlp::kInferRows - 1) / mlp::kInferRows;
     if (blocks > 0x7fffffffLL) return fail(CHERT_ERR_INVALID_ARG, "too many entries");
     CHERT_LAUNCH("k_warm_predict", k_warm_predict, dim3((unsigned)blocks), dim3(mlp::kThreads),
                  0, s, w, rows);
-    CHERT_LAUNCH("k_warm_solve", k_warm_solve, dim3((unsigned)jobs), dim3(64),
-                 (size_t)d->n_sweep * (sizeof(double2) + sizeof(int16_t)), s, w);
+    CHERT_LAUNCH("k_warm_solve", k_warm_solve, dim3((unsigned)jobs), dim3(64), 0, s, w);
     const int64_t grid = jobs < 4096 ? jobs : 4096;
+    CHERT_LAUNCH("k_warm_window", k_warm_window, dim3((unsigned)grid), dim3(64),
+                 kWinCap * (sizeof(double2) + sizeof(int16_t)) +
+                     (size_t)d->n_sweep * sizeof(int16_t), s, w);
     CHERT_LAUNCH("k_build_fused", k_build_fused, dim3((unsigned)grid), dim3(kNodeThreads),
                  (size_t)d->n_sweep * sizeof(double2), s, w.so, (const int32_t*)w.fb_list,
                  (const int32_t*)w.fb_len, jobs);

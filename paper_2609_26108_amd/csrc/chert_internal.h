@@ -53,6 +53,11 @@ int trace_batch_frontier(const chert_trace_job* jobs, int n_jobs, const chert_tr
 size_t trace_batch_frontier_bytes(const chert_trace_job* jobs, int n_jobs,
                                   const chert_trace_opts* o);
 
+// Smallest positive finite weight per field (wmin[2]) over weight tables laid
+// out [2][per_field]: init once, then one call per table (frontier.hip).
+int enqueue_wmin_init(double* wmin, hipStream_t s);
+int enqueue_wmin(const double* W, int64_t per_field, double* wmin, hipStream_t s);
+
 // 2D job checks shared by the tile and frontier paths (trace.hip).
 int validate_job_2d(const chert_trace_job& j, uint32_t outs);
 // Per-node weight table of a 2D job: W[f][j][o] = the edge j - o -> j

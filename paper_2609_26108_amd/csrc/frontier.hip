@@ -418,6 +418,19 @@ __global__ void k_front_tstar(RF a, int k) {
   }
 }
 
+// smallest positive weight of each field of a weight table (also for the
+// tile path's ordering): init once per call, then once per table
+int enqueue_wmin_init(double* wmin, hipStream_t s) {
+  CHERT_LAUNCH("k_front_wmin_init", k_front_wmin_init, dim3(1), dim3(64), 0, s, wmin);
+  return CHERT_OK;
+}
+int enqueue_wmin(const double* W, int64_t per_field, double* wmin, hipStream_t s) {
+  const int64_t blocks = (per_field + 255) / 256;
+  CHERT_LAUNCH("k_front_wmin", k_front_wmin, dim3((unsigned)(blocks > 1024 ? 1024 : blocks), 2),
+               dim3(256), 0, s, W, per_field, wmin);
+  return CHERT_OK;
+}
+
 // ------------------------------------------------------------------ plan --
 
 struct PlanF {
@@ -685,14 +698,11 @@ int trace_batch_frontier(const chert_trace_job* jobs, int n_jobs, const chert_tr
   a.R = P.R;
   CHERT_LAUNCH("k_front_clear", k_front_clear, dim3(64), dim3(256), 0, s, a.counts,
                P.max_iter + 2, a.err, a.stats);
-  CHERT_LAUNCH("k_front_wmin_init", k_front_wmin_init, dim3(1), dim3(64), 0, s, a.wmin);
+  enqueue_wmin_init(a.wmin, s);
   if (a.far) {
     for (int j = 0; j < n_jobs; ++j) {
       const int64_t rows = jd[j].per_node ? jd[j].n : jobs[j].n_classes * jobs[j].n_classes;
-      const int64_t per_field = rows * (int64_t)P.n_off;
-      const int64_t blocks = (per_field + 255) / 256;
-      CHERT_LAUNCH("k_front_wmin", k_front_wmin, dim3((unsigned)(blocks > 1024 ? 1024 : blocks), 2),
-                   dim3(256), 0, s, (const double*)(ws + P.off_W[j]), per_field, a.wmin);
+      enqueue_wmin((const double*)(ws + P.off_W[j]), rows * (int64_t)P.n_off, a.wmin, s);
     }
   }
   int64_t max_nodes = 0;

@@ -129,10 +129,14 @@ constexpr int kPX = kIn + 8;     // x  [32][16]
 constexpr int kPH = kHid + 8;    // h, d [32][128]
 constexpr int kPT = kRows + 8;   // transposed tiles [k][32]
 
-// inference tile: input and two ping-pong hidden buffers
+// inference: kInferRows samples per workgroup (each wavefront loads a weight
+// column block once and sweeps it over all row blocks); the hidden layers
+// are computed in place (every product is held in registers until the whole
+// tile has read its input)
+constexpr int kInferRows = 64;
 struct __align__(16) InferTile {
-  uint16_t x[kRows * kPX];
-  uint16_t h[2][kRows * kPH];
+  uint16_t x[kInferRows * kPX];
+  uint16_t h[kInferRows * kPH];
 };
 
 // training tile: activations in both orientations and one error buffer
@@ -176,11 +180,11 @@ __device__ __forceinline__ void hidden_layer(const uint16_t* in, int pin, const 
     }
 }
 
-// stage 32 standardised input rows (BF16) into the tile; src(r, i) is the
+// stage R standardised input rows (BF16) into the tile; src(r, i) is the
 // raw input i of row r, NaN for a padding row (staged as zero)
-template <bool kTrans, typename Src>
+template <bool kTrans, int R = kRows, typename Src>
 __device__ __forceinline__ void stage_x(const Net& n, uint16_t* tx, uint16_t* txt, Src src) {
-  for (int q = threadIdx.x; q < kRows * kIn; q += blockDim.x) {
+  for (int q = threadIdx.x; q < R * kIn; q += blockDim.x) {
     const int r = q / kIn, i = q % kIn;
     const float v = src(r, i);
     const uint16_t h = isnan(v) ? (uint16_t)0 : to_bf16((v - n.norm[i]) * n.norm[16 + i]);
@@ -189,25 +193,87 @@ __device__ __forceinline__ void stage_x(const Net& n, uint16_t* tx, uint16_t* tx
   }
 }
 
+// inference layer over kInferRows rows: out = tanh(in W + b); wavefront w
+// owns column blocks 2w and 2w + 1, keeps each one's weight fragments in
+// registers and runs it over every row block (same products, in the same
+// k order, as hidden_layer).  out may alias in: all threads pass a barrier
+// between the last read of in and the first write of out.
+template <int K>
+__device__ __forceinline__ void infer_layer(const uint16_t* in, int pin, const uint16_t* Wt,
+                                            const float* bias, uint16_t* out, int wave, int lane) {
+  constexpr int RB = kInferRows / 16;
+  f32x4 acc[2][RB];
+  for (int q = 0; q < 2; ++q) {
+    const int cb = 2 * wave + q;
+    if constexpr (K == 16) {
+      const s16x4 bv =
+          *reinterpret_cast<const s16x4*>(Wt + (cb * 16 + (lane & 15)) * K + 4 * (lane >> 4));
+      for (int rb = 0; rb < RB; ++rb) {
+        const s16x4 av = *reinterpret_cast<const s16x4*>(in + (rb * 16 + (lane & 15)) * pin +
+                                                         4 * (lane >> 4));
+        const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+        acc[q][rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, z, 0, 0, 0);
+      }
+    } else {
+      bf16x8 bv[K / 32];
+      const uint16_t* wb = Wt + (cb * 16 + (lane & 15)) * K + 8 * (lane >> 4);
+      for (int kk = 0; kk < K / 32; ++kk) bv[kk] = *reinterpret_cast<const bf16x8*>(wb + 32 * kk);
+      for (int rb = 0; rb < RB; ++rb) {
+        const uint16_t* a = in + (rb * 16 + (lane & 15)) * pin + 8 * (lane >> 4);
+        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+        for (int kk = 0; kk < K / 32; ++kk)
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(a + 32 * kk),
+                                                      bv[kk], c, 0, 0, 0);
+        acc[q][rb] = c;
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = 0; q < 2; ++q) {
+    const int col = (2 * wave + q) * 16 + acc_col(lane);
+    const float b = bias[col];
+    for (int rb = 0; rb < RB; ++rb)
+      for (int t = 0; t < 4; ++t)
+        out[(rb * 16 + acc_row(lane, t)) * kPH + col] = to_bf16(tanhf(acc[q][rb][t] + b));
+  }
+}
+
 // forward pass of a staged tile (all kThreads threads); store(r, c, v)
 // receives the de-standardised output c of row r
 template <typename Store>
 __device__ __forceinline__ void forward_infer(const Net& n, InferTile& t, Store store) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  hidden_layer<kIn>(t.x, kPX, n.fwd + fW1, n.master + oB1, t.h[0], nullptr, wave, lane);
+  infer_layer<kIn>(t.x, kPX, n.fwd + fW1, n.master + oB1, t.h, wave, lane);
   __syncthreads();
-  hidden_layer<kHid>(t.h[0], kPH, n.fwd + fW2, n.master + oB2, t.h[1], nullptr, wave, lane);
+  infer_layer<kHid>(t.h, kPH, n.fwd + fW2, n.master + oB2, t.h, wave, lane);
   __syncthreads();
-  hidden_layer<kHid>(t.h[1], kPH, n.fwd + fW3, n.master + oB3, t.h[0], nullptr, wave, lane);
+  infer_layer<kHid>(t.h, kPH, n.fwd + fW3, n.master + oB3, t.h, wave, lane);
   __syncthreads();
-  if (wave < 2) {
-    const f32x4 acc = mma_k32(t.h[0] + wave * 16 * kPH, kPH, n.fwd + fW4, kHid, kHid, lane);
-    const int col = acc_col(lane);
+  // output layer: one (padded) column block, row blocks spread over the waves
+  const int col = acc_col(lane);
+  bf16x8 bv[kHid / 32];
+  const uint16_t* wb = n.fwd + fW4 + (lane & 15) * kHid + 8 * (lane >> 4);
+  for (int kk = 0; kk < kHid / 32; ++kk) bv[kk] = *reinterpret_cast<const bf16x8*>(wb + 32 * kk);
+  for (int rb = wave; rb < kInferRows / 16; rb += kThreads / 64) {
+    const uint16_t* a = t.h + (rb * 16 + (lane & 15)) * kPH + 8 * (lane >> 4);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int kk = 0; kk < kHid / 32; ++kk)
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(a + 32 * kk),
+                                                    bv[kk], acc, 0, 0, 0);
     if (col < kOut)
       for (int tt = 0; tt < 4; ++tt)
-        store(wave * 16 + acc_row(lane, tt), col,
+        store(rb * 16 + acc_row(lane, tt), col,
               (acc[tt] + n.master[oB4 + col]) * n.norm[36 + col] + n.norm[32 + col]);
   }
+}
+
+// standardised BF16 input row r of an inference tile from its 16 raw inputs
+// (a padding row or a NaN input is staged as zero, as in stage_x)
+__device__ __forceinline__ void stage_row(const Net& n, uint16_t* tx, int r, const float* f,
+                                          bool pad) {
+  for (int i = 0; i < kIn; ++i)
+    tx[r * kPX + i] =
+        (pad || isnan(f[i])) ? (uint16_t)0 : to_bf16((f[i] - n.norm[i]) * n.norm[16 + i]);
 }
 
 // the 16 network inputs of (class, mode, local target ray angle)

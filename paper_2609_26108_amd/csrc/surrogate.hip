@@ -10,7 +10,7 @@
 //                  gradient and loss partial
 //   k_sg_reduce    sums the partials in workgroup order (deterministic)
 //   k_sg_adam      Adam on the FP32 master weights, refreshes BF16 copies
-//   k_sg_infer     forward of 32 samples per workgroup
+//   k_sg_infer     forward of 64 samples per workgroup
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -200,8 +200,8 @@ __global__ void __launch_bounds__(kThreads) k_sg_infer(const uint8_t* blob, cons
                                                        int64_t n_rows, float* y) {
   __shared__ InferTile t;
   const Net n = net_of(blob);
-  const int64_t base = (int64_t)blockIdx.x * kRows;
-  stage_x<false>(n, t.x, nullptr, [&](int r, int i) -> float {
+  const int64_t base = (int64_t)blockIdx.x * kInferRows;
+  stage_x<false, kInferRows>(n, t.x, nullptr, [&](int r, int i) -> float {
     return base + r < n_rows ? x[(base + r) * kIn + i] : NAN;
   });
   __syncthreads();
@@ -485,7 +485,7 @@ extern "C" int chert_surrogate_infer(const void* blob_dev, const float* x_dev, i
   if (rc) return rc;
   if (n < 0 || (n > 0 && (!x_dev || !y_dev))) return fail(CHERT_ERR_INVALID_ARG, "bad samples");
   if (n == 0) return CHERT_OK;
-  const int64_t blocks = (n + kRows - 1) / kRows;
+  const int64_t blocks = (n + kInferRows - 1) / kInferRows;
   if (blocks > 0x7fffffffLL) return fail(CHERT_ERR_INVALID_ARG, "too many samples");
   CHERT_LAUNCH("k_sg_infer", k_sg_infer, dim3((unsigned)blocks), dim3(kThreads), 0,
                (hipStream_t)stream, (const uint8_t*)blob_dev, x_dev, n, y_dev);

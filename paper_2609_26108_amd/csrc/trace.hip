@@ -25,6 +25,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -103,7 +104,22 @@ struct RelaxArgs {
   int32_t* err;      // out-of-range class ids seen
   unsigned long long* stats;  // [3 phases][2]: tile visits, raw edges examined
   int w_lds_doubles; // LDS room for W
+  // Tile ordering (bucket > 0): a tile activated with key k (the smallest
+  // value among the changed border nodes that woke it: tau, hop count or t*
+  // by phase) is visited in a round only if k <= its problem's smallest
+  // pending key + bucket * wmin (hop phase: + bucket hops); otherwise it
+  // waits, still active, for a later round.
+  unsigned long long* key;   // [2][n_tiles] keys (double bits) by round parity
+  unsigned long long* pmin;  // [3][n_prob] smallest key per problem, by round mod 3
+  const double* wmin;        // [2] smallest positive edge weight per field
+  double bucket;             // 0: every active tile is visited
 };
+
+constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;
+
+__device__ __forceinline__ unsigned long long dbits(double x) {
+  return (unsigned long long)__double_as_longlong(x);
+}
 
 // one tile visit of a phase: count it, the edges it examined and its push
 // levels (stats layout: [phase][visits, edges], then levels sum, levels max)
@@ -210,17 +226,20 @@ __global__ void k_init_fields(const ProbDev* probs, const JobDev* jobs, int32_t*
 }
 
 __global__ void k_clear_flags(int32_t* flags, int64_t n_flags, int32_t* counter, int n_counter,
-                              uint32_t* bar) {
+                              uint32_t* bar, unsigned long long* key, int64_t n_key,
+                              unsigned long long* pmin, int n_pmin) {
   int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t t = tid; t < n_flags; t += (int64_t)gridDim.x * blockDim.x) flags[t] = 0;
   for (int64_t t = tid; t < n_counter; t += (int64_t)gridDim.x * blockDim.x) counter[t] = 0;
+  for (int64_t t = tid; t < n_key; t += (int64_t)gridDim.x * blockDim.x) key[t] = kInfBits;
+  for (int64_t t = tid; t < n_pmin; t += (int64_t)gridDim.x * blockDim.x) pmin[t] = kInfBits;
   if (tid < 3) bar[tid] = 0u;  // barrier arrivals, generation, abort
 }
 
 // activate the source tile of every problem (t* phase: only problems with t*)
 __global__ void k_seed_flags(int32_t* flags, int32_t* list, int32_t* counter,
                              const ProbDev* probs, const JobDev* jobs, int n_prob, int tx, int tz,
-                             int tstar_phase) {
+                             int tstar_phase, unsigned long long* key, unsigned long long* pmin) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_prob) return;
   const ProbDev pr = probs[p];
@@ -230,6 +249,8 @@ __global__ void k_seed_flags(int32_t* flags, int32_t* list, int32_t* counter,
   const int T = pr.tile_base + (sz / tz) * jb.ntx + (sx / tx);
   flags[T] = kFlagActive | kFlagSeed;
   list[atomicAdd(&counter[0], 1)] = T;
+  key[T] = 0ull;  // the source's value: visited in round 0
+  pmin[p] = 0ull;
 }
 
 // --------------------------------------------------------- tile helpers ---
@@ -243,15 +264,20 @@ struct TileCtx {
 
 // Claim this workgroup's (problem, tile) for the round: find the problem by
 // binary search over the tile bases, read and clear the tile's flag.
+__device__ __forceinline__ double key_delta(const RelaxArgs& a, int phase, int field) {
+  if (phase == 1) return a.bucket;  // hop counts
+  const double w = a.wmin[phase == 2 ? kFieldI : field];
+  return w < INFINITY ? a.bucket * w : INFINITY;
+}
+
 __device__ __forceinline__ TileCtx tile_begin(const RelaxArgs& a, int round, int T, int* s_flag,
-                                              int* s_prob) {
+                                              int* s_prob, int phase) {
   // Plain round-robin order: the active tiles of a round form a compact
   // wavefront band, and dealing consecutive tiles to different XCDs spreads
   // that band over all of them (banding tiles per XCD measured slower).
   int32_t* fin = a.flags + (int64_t)(round & 1) * a.n_tiles;
   if (threadIdx.x == 0) {
     int32_t f = fin[T];
-    *s_flag = f;
     if (f) {
       fin[T] = 0;
       int lo = 0, hi = a.n_prob - 1;
@@ -261,7 +287,24 @@ __device__ __forceinline__ TileCtx tile_begin(const RelaxArgs& a, int round, int
         else hi = mid - 1;
       }
       *s_prob = lo;
+      if (a.bucket > 0.0) {
+        unsigned long long* kin = a.key + (int64_t)(round & 1) * a.n_tiles;
+        const unsigned long long k = kin[T];
+        kin[T] = kInfBits;
+        const double lim = __longlong_as_double((long long)a.pmin[(round % 3) * a.n_prob + lo]) +
+                           key_delta(a, phase, a.probs[lo].field);
+        if (!(__longlong_as_double((long long)k) <= lim)) {
+          // not yet: still active next round, with the same key
+          const int64_t nxt = (int64_t)((round + 1) & 1) * a.n_tiles;
+          if (atomicOr(&a.flags[nxt + T], f) == 0)
+            a.list[nxt + atomicAdd(&a.counter[round + 1], 1)] = T;
+          atomicMin(&a.key[nxt + T], k);
+          atomicMin(&a.pmin[((round + 1) % 3) * a.n_prob + lo], k);
+          f = 0;
+        }
+      }
     }
+    *s_flag = f;
   }
   __syncthreads();
   TileCtx c;
@@ -296,8 +339,14 @@ __device__ __forceinline__ int border_bits(int x, int z, int tx, int tz, int R) 
 }
 
 __device__ __forceinline__ void activate(const RelaxArgs& a, int round, const TileCtx& c,
-                                         const ProbDev& pr, const JobDev& jb, int mask) {
+                                         const ProbDev& pr, const JobDev& jb, int mask,
+                                         unsigned long long key) {
   int32_t* fout = a.flags + (int64_t)((round + 1) & 1) * a.n_tiles;
+  if (a.bucket > 0.0) {
+    // this tile again (iteration cap): key 0 keeps it in the next round
+    if (mask & (1 << 4)) key = 0ull;
+    atomicMin(&a.pmin[((round + 1) % 3) * a.n_prob + c.p], key);
+  }
   for (int bit = 0; bit < 9; ++bit) {
     if (!(mask & (1 << bit))) continue;
     int dx = bit % 3 - 1, dz = bit / 3 - 1;
@@ -305,10 +354,21 @@ __device__ __forceinline__ void activate(const RelaxArgs& a, int round, const Ti
     if (nx_ < 0 || nx_ >= jb.ntx || nz_ < 0 || nz_ >= jb.ntz) continue;
     int32_t* f = &fout[pr.tile_base + nz_ * jb.ntx + nx_];
     const int32_t bits = (bit == 4) ? (kFlagActive | kFlagFull) : kFlagActive;
+    if (a.bucket > 0.0)
+      atomicMin(&a.key[(int64_t)((round + 1) & 1) * a.n_tiles + pr.tile_base + nz_ * jb.ntx + nx_],
+                key);
     if (atomicOr(f, bits) == 0)
       a.list[(int64_t)((round + 1) & 1) * a.n_tiles + atomicAdd(&a.counter[round + 1], 1)] =
           pr.tile_base + nz_ * jb.ntx + nx_;
   }
+}
+
+// Smallest pending key of each problem for round + 2 starts over (round
+// round + 1 fills it; it was last read in round - 1).  Block 0 of a round.
+__device__ __forceinline__ void reset_pmin(const RelaxArgs& a, int round) {
+  if (a.bucket <= 0.0) return;
+  unsigned long long* pm = a.pmin + (int64_t)((round + 2) % 3) * a.n_prob;
+  for (int p = threadIdx.x; p < a.n_prob; p += blockDim.x) pm[p] = kInfBits;
 }
 
 struct Smem {
@@ -397,9 +457,6 @@ __device__ __forceinline__ void frontier_add(bool flag, int node, int32_t* list,
 }
 
 
-__device__ __forceinline__ unsigned long long dbits(double x) {
-  return (unsigned long long)__double_as_longlong(x);
-}
 
 // Does this visit pull node ml (LDS index)?  Border band, or all on kFlagFull.
 __device__ __forceinline__ bool pulls(const RelaxArgs& a, const TileCtx& c, int ml) {
@@ -449,7 +506,8 @@ template <int G>
 __device__ __forceinline__ void relax_tau(const RelaxArgs& a, int round, int T) {
   extern __shared__ double smem_d[];
   __shared__ int s_flag, s_prob, s_mask, s_cnt[3];
-  const TileCtx c = tile_begin(a, round, T, &s_flag, &s_prob);
+  __shared__ unsigned long long s_key;
+  const TileCtx c = tile_begin(a, round, T, &s_flag, &s_prob, 0);
   if (!c.active) return;
   const Smem s = carve(a, smem_d);
   const int R = a.R, lw = a.lw, n = lw * a.lh, n_off = a.n_off;
@@ -457,6 +515,7 @@ __device__ __forceinline__ void relax_tau(const RelaxArgs& a, int round, int T) 
   const JobDev jb = a.jobs[pr.job];
   if (threadIdx.x == 0) {
     s_mask = 0;
+    s_key = kInfBits;
     s_cnt[0] = 0;
     s_cnt[1] = 0;
     s_cnt[2] = 0;
@@ -569,12 +628,14 @@ __device__ __forceinline__ void relax_tau(const RelaxArgs& a, int round, int T) 
   if (ml >= 0 && s.val[ml] < orig) {
     int x = ml % lw - R, z = ml / lw - R;
     pr.tau[(int64_t)(c.x0 + x) + (int64_t)jb.nx * (c.z0 + z)] = s.val[ml];
-    mask |= border_bits(x, z, a.tx, a.tz, R);
+    const int bb = border_bits(x, z, a.tx, a.tz, R);
+    mask |= bb;
+    if (bb && a.bucket > 0.0) atomicMin(&s_key, dbits(s.val[ml]));
   }
   count_visit(a, 0, raw, it - 1);
   if (mask) atomicOr(&s_mask, mask);
   __syncthreads();
-  if (threadIdx.x == 0 && s_mask) activate(a, round, c, pr, jb, s_mask);
+  if (threadIdx.x == 0 && s_mask) activate(a, round, c, pr, jb, s_mask, s_key);
 }
 
 // Phase HOP: BFS hop counts over tight edges, h_j <- min(h_j, h_i + 1).
@@ -582,7 +643,8 @@ template <int G>
 __device__ __forceinline__ void relax_hop(const RelaxArgs& a, int round, int T) {
   extern __shared__ double smem_d[];
   __shared__ int s_flag, s_prob, s_mask, s_cnt[3];
-  const TileCtx c = tile_begin(a, round, T, &s_flag, &s_prob);
+  __shared__ unsigned long long s_key;
+  const TileCtx c = tile_begin(a, round, T, &s_flag, &s_prob, 1);
   if (!c.active) return;
   const Smem s = carve(a, smem_d);
   const int R = a.R, lw = a.lw, n = lw * a.lh, n_off = a.n_off;
@@ -590,6 +652,7 @@ __device__ __forceinline__ void relax_hop(const RelaxArgs& a, int round, int T) 
   const JobDev jb = a.jobs[pr.job];
   if (threadIdx.x == 0) {
     s_mask = 0;
+    s_key = kInfBits;
     s_cnt[0] = 0;
     s_cnt[1] = 0;
     s_cnt[2] = 0;
@@ -704,12 +767,14 @@ __device__ __forceinline__ void relax_hop(const RelaxArgs& a, int round, int T) 
   if (ml >= 0 && s.ival[ml] < orig) {
     int x = ml % lw - R, z = ml / lw - R;
     pr.hop[(int64_t)(c.x0 + x) + (int64_t)jb.nx * (c.z0 + z)] = s.ival[ml];
-    mask |= border_bits(x, z, a.tx, a.tz, R);
+    const int bb = border_bits(x, z, a.tx, a.tz, R);
+    mask |= bb;
+    if (bb && a.bucket > 0.0) atomicMin(&s_key, dbits((double)s.ival[ml]));
   }
   count_visit(a, 1, raw, it - 1);
   if (mask) atomicOr(&s_mask, mask);
   __syncthreads();
-  if (threadIdx.x == 0 && s_mask) activate(a, round, c, pr, jb, s_mask);
+  if (threadIdx.x == 0 && s_mask) activate(a, round, c, pr, jb, s_mask, s_key);
 }
 
 // pred_j = tight in-neighbour with hop_j - 1 and the smallest offset index.
@@ -774,7 +839,8 @@ template <int G>
 __device__ __forceinline__ void relax_tstar(const RelaxArgs& a, int round, int T) {
   extern __shared__ double smem_d[];
   __shared__ int s_flag, s_prob, s_mask, s_cnt[3];
-  const TileCtx c = tile_begin(a, round, T, &s_flag, &s_prob);
+  __shared__ unsigned long long s_key;
+  const TileCtx c = tile_begin(a, round, T, &s_flag, &s_prob, 2);
   if (!c.active) return;
   const Smem s = carve(a, smem_d);
   const int R = a.R, lw = a.lw, n = lw * a.lh, n_off = a.n_off;
@@ -783,6 +849,7 @@ __device__ __forceinline__ void relax_tstar(const RelaxArgs& a, int round, int T
   const JobDev jb = a.jobs[pr.job];
   if (threadIdx.x == 0) {
     s_mask = 0;
+    s_key = kInfBits;
     s_cnt[0] = 0;
     s_cnt[1] = 0;
     s_cnt[2] = 0;
@@ -884,27 +951,53 @@ __device__ __forceinline__ void relax_tstar(const RelaxArgs& a, int round, int T
     int64_t g = (int64_t)(c.x0 + x) + (int64_t)jb.nx * (c.z0 + z);
     if (isnan(pr.tstar[g])) {
       pr.tstar[g] = s.val[ml];
-      mask |= border_bits(x, z, a.tx, a.tz, R);
+      const int bb = border_bits(x, z, a.tx, a.tz, R);
+      mask |= bb;
+      if (bb && a.bucket > 0.0) atomicMin(&s_key, dbits(s.val[ml]));
     }
   }
   count_visit(a, 2, raw, it - 1);
   if (mask) atomicOr(&s_mask, mask);
   __syncthreads();
-  if (threadIdx.x == 0 && s_mask) activate(a, round, c, pr, jb, s_mask);
+  if (threadIdx.x == 0 && s_mask) activate(a, round, c, pr, jb, s_mask, s_key);
 }
 
-// One launch per round: one workgroup per tile of every problem.
+// One launch per round.  With one workgroup per tile (grid = n_tiles) tile T
+// is always visited by workgroup T, so it stays on one XCD and its interior
+// values from the last visit can still be in that XCD's L2; with a smaller
+// grid (large batches: fewer dispatches) the workgroups walk the round's
+// active-tile list.
+template <int G, int PH>
+__device__ __forceinline__ void visit(const RelaxArgs& a, int round, int T) {
+  if constexpr (PH == 0) relax_tau<G>(a, round, T);
+  else if constexpr (PH == 1) relax_hop<G>(a, round, T);
+  else relax_tstar<G>(a, round, T);
+}
+template <int G, int PH>
+__device__ __forceinline__ void round_tiles(const RelaxArgs& a, int round) {
+  if (blockIdx.x == 0) reset_pmin(a, round);
+  if ((int)gridDim.x == a.n_tiles) {
+    visit<G, PH>(a, round, blockIdx.x);  // inactive tiles leave at once
+    return;
+  }
+  const int n_act = a.counter[round];
+  const int32_t* lst = a.list + (int64_t)(round & 1) * a.n_tiles;
+  for (int i = blockIdx.x; i < n_act; i += gridDim.x) {
+    visit<G, PH>(a, round, lst[i]);
+    __syncthreads();  // LDS is reused by the next tile
+  }
+}
 template <int G>
 __global__ void __launch_bounds__(kRelaxThreads) k_relax_tau(RelaxArgs a, int round) {
-  relax_tau<G>(a, round, blockIdx.x);
+  round_tiles<G, 0>(a, round);
 }
 template <int G>
 __global__ void __launch_bounds__(kRelaxThreads) k_relax_hop(RelaxArgs a, int round) {
-  relax_hop<G>(a, round, blockIdx.x);
+  round_tiles<G, 1>(a, round);
 }
 template <int G>
 __global__ void __launch_bounds__(kRelaxThreads) k_relax_tstar(RelaxArgs a, int round) {
-  relax_tstar<G>(a, round, blockIdx.x);
+  round_tiles<G, 2>(a, round);
 }
 
 // ------------------------------------------------- persistent launch ---
@@ -963,6 +1056,7 @@ __device__ __forceinline__ bool grid_barrier(const PersistArgs& p) {
 template <int G, int PH>
 __global__ void __launch_bounds__(kRelaxThreads) k_relax_persist(RelaxArgs a, PersistArgs p) {
   for (int round = 0; round < p.max_rounds; ++round) {
+    if (blockIdx.x == 0) reset_pmin(a, round);
     const int n_act =
         __hip_atomic_load(&a.counter[round], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int32_t* lst = a.list + (int64_t)(round & 1) * a.n_tiles;
@@ -1020,7 +1114,7 @@ struct Plan {
   std::vector<int64_t> nodes;  // per job
   std::vector<int> ntx, ntz, K;
   size_t off_star = 0, off_lbin = 0, off_jobs = 0, off_probs = 0, off_flags = 0, off_list = 0,
-         off_counter = 0,
+         off_counter = 0, off_key = 0, off_pmin = 0, off_wmin = 0,
          off_err = 0, off_hop = 0, total = 0;
   std::vector<size_t> off_W;  // per job
   int w_lds_doubles = 0;
@@ -1066,6 +1160,8 @@ static int validate_opts(const chert_trace_opts* o) {
     return fail(CHERT_ERR_INVALID_ARG, "push_group must be 0, 1, 2 or 4");
   if (o->launch != CHERT_LAUNCH_PER_ROUND && o->launch != CHERT_LAUNCH_PERSISTENT)
     return fail(CHERT_ERR_INVALID_ARG, "launch must be CHERT_LAUNCH_PER_ROUND or _PERSISTENT");
+  if (!(o->bucket_width >= 0.0) || !isfinite(o->bucket_width))
+    return fail(CHERT_ERR_INVALID_ARG, "bucket_width must be finite and >= 0");
   uint32_t outs = o->outputs;
   if (outs == 0 || (outs & ~31u)) return fail(CHERT_ERR_INVALID_ARG, "bad output mask");
   if ((outs & CHERT_OUT_TSTAR) && !((outs & CHERT_OUT_TAU_R) && (outs & CHERT_OUT_PRED_P)))
@@ -1119,7 +1215,10 @@ static int make_plan(const chert_trace_job* jobs, int n_jobs, const chert_trace_
   if (P->n_tiles >= 0x7fffffffLL || P->n_prob > 65535)
     return fail(CHERT_ERR_UNSUPPORTED, "batch too large for one launch");
   P->w_lds_doubles = w_lds;
-  P->max_rounds = (o->max_rounds > 0) ? o->max_rounds : 1024 + 64 * (int)max_tile_span;
+  // ordered tiles wait for their turn: more rounds, fewer visits
+  P->max_rounds = (o->max_rounds > 0)
+                      ? o->max_rounds
+                      : 1024 + 64 * (int)max_tile_span + (o->bucket_width > 0.0 ? 8192 : 0);
   size_t off = 0;
   P->off_star = off;
   off += align256((size_t)kMaxOffsets * 2 * sizeof(int32_t));
@@ -1135,6 +1234,12 @@ static int make_plan(const chert_trace_job* jobs, int n_jobs, const chert_trace_
   off += align256((size_t)2 * P->n_tiles * sizeof(int32_t));
   P->off_counter = off;
   off += align256((size_t)(P->max_rounds + 2) * sizeof(int32_t));
+  P->off_key = off;
+  off += align256((size_t)2 * P->n_tiles * sizeof(uint64_t));
+  P->off_pmin = off;
+  off += align256((size_t)3 * P->n_prob * sizeof(uint64_t));
+  P->off_wmin = off;
+  off += 256;
   P->off_err = off;
   off += 256;
   for (int j = 0; j < n_jobs; ++j) {
@@ -1151,14 +1256,14 @@ static int make_plan(const chert_trace_job* jobs, int n_jobs, const chert_trace_
 }
 
 static int run_rounds(hipStream_t s, const RelaxArgs& a, void (*kern)(RelaxArgs, int),
-                      const char* name, size_t lds, int max_rounds, int* rounds) {
+                      const char* name, int grid, size_t lds, int max_rounds, int* rounds) {
   const int batch = 8;
   int32_t counts[batch];
   for (int r = 0; r < max_rounds; r += batch) {
     int nb = batch;
     if (r + nb > max_rounds) nb = max_rounds - r;
     for (int q = 0; q < nb; ++q)
-      CHERT_LAUNCH(name, kern, dim3((unsigned)a.n_tiles), dim3(kRelaxThreads), lds, s, a, r + q);
+      CHERT_LAUNCH(name, kern, dim3((unsigned)grid), dim3(kRelaxThreads), lds, s, a, r + q);
     hipError_t e = hipMemcpyAsync(counts, a.counter + r + 1, sizeof(int32_t) * nb,
                                   hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1221,6 +1326,7 @@ struct Prepared {
   double* dL = nullptr;
   int32_t* dcol = nullptr;
   int pgrid[3] = {0, 0, 0};  // persistent-launch grid per phase
+  int rgrid[3] = {0, 0, 0};  // per-round launch grid per phase
 };
 
 // Plan the batch and upload its tables (synchronous on s).
@@ -1339,6 +1445,10 @@ static int prepare(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
   a.err = (int32_t*)(ws + P.off_err);
   a.stats = (unsigned long long*)(ws + P.off_err + 64);
   a.w_lds_doubles = P.w_lds_doubles;
+  a.key = (unsigned long long*)(ws + P.off_key);
+  a.pmin = (unsigned long long*)(ws + P.off_pmin);
+  a.wmin = (const double*)(ws + P.off_wmin);
+  a.bucket = o->bucket_width;
   Q->lds = lds_bytes(P.lw, P.lh, P.w_lds_doubles, P.n_off, P.tx, P.tz);
   Q->pa.max_rounds = P.max_rounds;
   Q->pa.bar = (uint32_t*)(ws + P.off_err + 192);
@@ -1350,12 +1460,17 @@ static int prepare(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
   Q->doz = doz;
   Q->dL = dL;
   Q->dcol = dcol;
-  if (o->launch == CHERT_LAUNCH_PERSISTENT) {
-    const int G = o->push_group ? o->push_group : 2;
-    for (int ph = 0; ph < 3; ++ph) {
+  const int G = o->push_group ? o->push_group : 2;
+  for (int ph = 0; ph < 3; ++ph) {
+    if (o->launch == CHERT_LAUNCH_PERSISTENT)
       rc = persist_grid((const void*)persist_kernel(ph, G), Q->lds, P.n_tiles, &Q->pgrid[ph]);
-      if (rc) return rc;
-    }
+    else
+      rc = persist_grid((const void*)round_kernel(ph, G), Q->lds, P.n_tiles, &Q->rgrid[ph]);
+    if (rc) return rc;
+    // per-round launches: one workgroup per tile while that is at most 4x
+    // the resident workgroups (tile affinity), else 4x the resident
+    // workgroups walking the active list
+    Q->rgrid[ph] = (int)std::min<int64_t>(P.n_tiles, 4 * (int64_t)Q->rgrid[ph]);
   }
   return CHERT_OK;
 }
@@ -1399,6 +1514,13 @@ static int enqueue(const Prepared& Q, const chert_trace_job* jobs, int n_jobs,
                    n_cols, Q.dL + (size_t)j * kMaxOffsets, Q.dcol + (size_t)j * kMaxOffsets);
     }
   }
+  if (a.bucket > 0.0) {  // the ordering's unit: smallest edge weight per field
+    enqueue_wmin_init((double*)a.wmin, s);
+    for (int j = 0; j < n_jobs; ++j) {
+      const int64_t rows = Q.jd[j].per_node ? P.nodes[j] : (int64_t)Q.jd[j].K * Q.jd[j].K;
+      enqueue_wmin((const double*)(ws + P.off_W[j]), rows * P.n_off, (double*)a.wmin, s);
+    }
+  }
   int64_t max_nodes = 0;
   for (int64_t n : P.nodes) max_nodes = n > max_nodes ? n : max_nodes;
   const unsigned gx = (unsigned)((max_nodes + 255) / 256 > 1024 ? 1024 : (max_nodes + 255) / 256);
@@ -1408,10 +1530,11 @@ static int enqueue(const Prepared& Q, const chert_trace_job* jobs, int n_jobs,
   const int64_t n_flags = 2 * P.n_tiles;
   auto init_flags = [&](int tstar_phase) {
     CHERT_LAUNCH("k_clear_flags", k_clear_flags, dim3(256), dim3(256), 0, s, a.flags, n_flags,
-                 a.counter, P.max_rounds + 2, pa.bar);
+                 a.counter, P.max_rounds + 2, pa.bar, a.key, 2 * P.n_tiles, a.pmin,
+                 3 * P.n_prob);
     CHERT_LAUNCH("k_seed_flags", k_seed_flags, dim3((P.n_prob + 63) / 64), dim3(64), 0, s,
                  a.flags, a.list, a.counter, Q.dprobs, Q.djobs, P.n_prob, P.tx, P.tz,
-                 tstar_phase);
+                 tstar_phase, a.key, a.pmin);
   };
   const int G = o->push_group ? o->push_group : 2;
   static const char* kname[3] = {"k_relax_tau", "k_relax_hop", "k_relax_tstar"};
@@ -1425,7 +1548,8 @@ static int enqueue(const Prepared& Q, const chert_trace_job* jobs, int n_jobs,
       rounds[ph] = 0;  // read back by finish()
       return CHERT_OK;
     }
-    return run_rounds(s, a, round_kernel(ph, G), kname[ph], lds, P.max_rounds, &rounds[ph]);
+    return run_rounds(s, a, round_kernel(ph, G), kname[ph], Q.rgrid[ph], lds, P.max_rounds,
+                      &rounds[ph]);
   };
   int rc = phase(0);
   if (rc) return rc;
@@ -1579,6 +1703,7 @@ const int kTuneLaunch[] = {CHERT_LAUNCH_PER_ROUND, CHERT_LAUNCH_PERSISTENT};
 
 const double kTuneBuckets[] = {0.0, 4.0, 16.0, 32.0, 64.0, 128.0, 256.0};
 const double kTuneBuckets2D[] = {0.0, 16.0, 64.0};  // 2D: the tiles usually win
+const double kTuneTileBuckets[] = {16.0, 64.0, 256.0};
 
 extern "C" size_t chert_trace_autotune_workspace_bytes(const chert_trace_job* jobs,
                                                        int32_t n_jobs,
@@ -1595,6 +1720,7 @@ extern "C" size_t chert_trace_autotune_workspace_bytes(const chert_trace_job* jo
     c.tile_x = t[0];
     c.tile_z = t[1];
     c.launch = CHERT_LAUNCH_PER_ROUND;
+    c.bucket_width = 1.0;  // ordered tiles: the larger round counter array
     const size_t b = chert_trace_batch_workspace_bytes(jobs, n_jobs, &c);
     if (b > best) best = b;
   }
@@ -1629,6 +1755,7 @@ extern "C" int chert_trace_autotune(const chert_trace_job* jobs, int32_t n_jobs,
           c.tile_z = t[1];
           c.push_group = G;
           c.launch = L;
+          c.bucket_width = 0.0;
           cands.push_back(c);
         }
   hipEvent_t e0, e1;
@@ -1637,10 +1764,10 @@ extern "C" int chert_trace_autotune(const chert_trace_job* jobs, int32_t n_jobs,
   double best = -1.0;
   chert_trace_opts pick = *o;
   int tried = 0;
-  for (chert_trace_opts c : cands) {
+  auto consider = [&](chert_trace_opts c) {
     c.stats_host = nullptr;
     const size_t need = chert_trace_batch_workspace_bytes(probe.data(), n_jobs, &c);
-    if (need == 0 || need > workspace_bytes) continue;  // shape not valid here
+    if (need == 0 || need > workspace_bytes) return;  // shape not valid here
     int rc = CHERT_OK;
     float ms = 0.f;
     for (int rep = 0; rep < 2 && rc == CHERT_OK; ++rep) {  // second run is timed
@@ -1650,13 +1777,21 @@ extern "C" int chert_trace_autotune(const chert_trace_job* jobs, int32_t n_jobs,
       if (hipEventSynchronize(e1) != hipSuccess) rc = CHERT_ERR_HIP;
       if (rc == CHERT_OK) (void)hipEventElapsedTime(&ms, e0, e1);
     }
-    if (rc != CHERT_OK) continue;
+    if (rc != CHERT_OK) return;
     ++tried;
     if (best < 0.0 || ms < best) {
       best = ms;
       pick = c;
     }
-  }
+  };
+  for (const chert_trace_opts& c : cands) consider(c);
+  // tiles: then the ordering width for the fastest shape
+  if (tried > 0 && pick.launch != CHERT_LAUNCH_FRONTIER)
+    for (double bw : kTuneTileBuckets) {
+      chert_trace_opts c = pick;
+      c.bucket_width = bw;
+      consider(c);
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (tried == 0) return fail(CHERT_ERR_INVALID_ARG, "no candidate fits the workspace");

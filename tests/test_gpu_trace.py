@@ -70,20 +70,23 @@ def imported_case(G, model, modes, tile=(0, 0), sources=None, n_sweep=1440, laun
             assert_fields_equal(g, o, si)
 
 
-@pytest.mark.parametrize("launch,bucket", [(0, 0.0), (1, 0.0), (2, 0.0), (2, 8.0)])
+@pytest.mark.parametrize("launch,bucket", [(0, 0.0), (1, 0.0), (0, 4.0), (1, 16.0), (2, 0.0),
+                                           (2, 8.0)])
 def test_imported_cache_small_layered_bitwise(G, launch, bucket):
     """Every launch form (one launch per round; one persistent launch per
-    phase; the node frontier with one bucket or near/far buckets) reaches the
-    oracle's fields bitwise."""
+    phase; either with tiles visited in key order; the node frontier with one
+    bucket or near/far buckets) reaches the oracle's fields bitwise."""
     m = W.small_layered()
     imported_case(G, m, (0, 1, 2), launch=launch, bucket=bucket)
 
 
-@pytest.mark.parametrize("tile", [(8, 8), (16, 4), (32, 16), (64, 16)])
-def test_tile_shapes_give_identical_fields(G, tile):
-    """Determinism across schedules: every tile shape reaches the same bits."""
+@pytest.mark.parametrize("tile,bucket", [((8, 8), 0.0), ((16, 4), 0.0), ((32, 16), 0.0),
+                                         ((64, 16), 0.0), ((8, 8), 2.0), ((16, 4), 32.0)])
+def test_tile_shapes_give_identical_fields(G, tile, bucket):
+    """Determinism across schedules: every tile shape and ordering width
+    reaches the same bits."""
     m = W.small_layered(nx=53, nz=29, radius=4, seed=3)
-    imported_case(G, m, (1,), tile=tile)
+    imported_case(G, m, (1,), tile=tile, bucket=bucket)
 
 
 def test_multiple_sources_one_call(G):
@@ -210,7 +213,8 @@ def check_batch(jobs):
             assert_fields_equal(g, o, si)
 
 
-@pytest.mark.parametrize("launch,bucket", [(0, 0.0), (1, 0.0), (2, 0.0), (2, 16.0)])
+@pytest.mark.parametrize("launch,bucket", [(0, 0.0), (1, 0.0), (0, 8.0), (1, 64.0), (2, 0.0),
+                                           (2, 16.0)])
 def test_batch_uneven_grids_modes_sources_bitwise(G, launch, bucket):
     """chert_trace_batch over uneven grids, modes and sources: every field
     bitwise equal to the oracle, in every launch form."""
@@ -230,13 +234,15 @@ def test_batch_uneven_grids_modes_sources_bitwise(G, launch, bucket):
     check_batch(jobs)
 
 
-def test_graph_replays_match_eager(G):
+@pytest.mark.parametrize("bucket", [0.0, 16.0])
+def test_graph_replays_match_eager(G, bucket):
     """The batch captured as one graph: three replays, each after eager work
     of the program's own and a wipe of the outputs, equal the eager
-    persistent run bitwise (and so the oracle)."""
+    persistent run bitwise (and so the oracle), with or without tile
+    ordering."""
     Cm = C()
     b, jobs, keep = uneven_batch(G)
-    opts = Cm.trace_opts(Cm.OUT_ALL, launch=Cm.LAUNCH_PERSISTENT)
+    opts = Cm.trace_opts(Cm.OUT_ALL, launch=Cm.LAUNCH_PERSISTENT, bucket_width=bucket)
     ws = torch.empty(Cm.chert_trace_batch_workspace_bytes(b, opts), dtype=torch.uint8,
                      device=G.DEV)
     Cm.chert_trace_batch(b, opts, ws)
@@ -283,6 +289,7 @@ def test_autotuned_options_give_identical_fields(G):
         assert opts.bucket_width in (0.0, 16.0, 64.0)
     else:
         assert opts.push_group in (1, 2, 4) and opts.tile_x * opts.tile_z <= 1024
+        assert opts.bucket_width in (0.0, 16.0, 64.0, 256.0)
     for j in jobs:
         for t in j[5].values():
             t.fill_(-3)
@@ -291,7 +298,7 @@ def test_autotuned_options_give_identical_fields(G):
     check_batch(jobs)
 
 
-@pytest.mark.parametrize("launch,bucket", [(0, 0.0), (2, 0.0), (2, 16.0)])
+@pytest.mark.parametrize("launch,bucket", [(0, 0.0), (0, 8.0), (1, 32.0), (2, 0.0), (2, 16.0)])
 def test_per_node_trace_bitwise(G, launch, bucket):
     """Per-node cache (no class map): GPU traveltimes and predecessors on an
     imported oracle cache are bitwise the oracle's, on the tiles and on the
