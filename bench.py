@@ -39,12 +39,12 @@ FP64_VALU_PEAK_TOPS = 39.3  # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz, one o
 # Valid only for the kernel source it was measured on.
 MEASURED_TRAFFIC = {
     "source": "paper_2609_26108_amd/csrc/trace.hip",
-    "source_sha256_16": "92eb424bf739df69",
+    "source_sha256_16": "f46395b9bb8c4f2a",
     "fetch_scale": 2.0, "write_scale": 1.0,
     "kib_per_dispatch": {  # kernel -> (FETCH_SIZE KiB, WRITE_SIZE KiB)
-        "k_relax_tau": (2424.3, 731.3),
-        "k_relax_hop": (3036.7, 233.1),
-        "k_relax_tstar": (1564.3, 173.9),
+        "k_relax_tau": (2438.8, 731.3),
+        "k_relax_hop": (3053.1, 233.1),
+        "k_relax_tstar": (1576.4, 173.9),
     },
 }
 
@@ -59,6 +59,34 @@ def measured_traffic_bytes(kernel):
     if kib is None or h != MEASURED_TRAFFIC["source_sha256_16"]:
         return None
     return 1024.0 * (kib[0] * MEASURED_TRAFFIC["fetch_scale"] + kib[1] * MEASURED_TRAFFIC["write_scale"])
+
+
+# Executed FP64 work per dispatch of the surrogate-started build's kernels on
+# the structurally complex workload (`bench.py --workload complex2d`), from
+# rocprofv3 --pmc SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64
+# SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_TRANS_F64 (see profiles/): wave
+# instructions x 64 lanes, an FMA counted as two flops (lanes masked off by
+# divergence count as executed).  Valid only for the sources it was measured
+# on.
+MEASURED_FP64 = {
+    "sources": ["paper_2609_26108_amd/csrc/cache_build.hip",
+                "paper_2609_26108_amd/csrc/physics.h", "paper_2609_26108_amd/csrc/mlp.h"],
+    "sources_sha256_16": "1b6627ce68c0eb0f",
+    "flops_per_dispatch": {"k_warm_solve": 7.4710e11, "k_warm_window": 5.4837e11,
+                           "k_warm_predict": 5.3496e9},
+}
+
+
+def measured_fp64_flops(kernel):
+    """Executed FP64 flops per dispatch, or None if not measured for the
+    current sources."""
+    import hashlib
+    h = hashlib.sha256()
+    for src in MEASURED_FP64["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest()[:16] != MEASURED_FP64["sources_sha256_16"]:
+        return None
+    return MEASURED_FP64["flops_per_dispatch"].get(kernel)
 
 
 def useful_edges(nx, nz, ox, oz):
@@ -429,6 +457,22 @@ def run_complex(args):
                    "hamiltonian_solves_per_s": conv_warm / t_warm, "stats": wstats,
                    "fallback_job_frac": wstats["fallback_jobs"] / max(wstats["jobs"], 1),
                    "kernels_ms": {k: v[1] for k, v in pw.items()}}
+    # roofline of the build's dominant kernel: FP64 VALU work (executed
+    # flops from the committed counter profile) over its live launch time
+    dom = max(pw, key=lambda k: pw[k][1])
+    fl = measured_fp64_flops(dom)
+    avg_s = 1e-3 * pw[dom][1] / max(pw[dom][0], 1)
+    ach = fl / avg_s / 1e12 if fl else None
+    out["roofline"] = {
+        "kernel": dom, "bound": "fp64", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
+        "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS if ach else None, "traffic": None,
+        "avg_launch_us": 1e6 * avg_s,
+        "work_per_launch": (f"{fl:.4g} executed FP64 flops (counters, 64 lanes per wave "
+                            "instruction, FMA = 2)") if fl else None,
+        "build_fp64_tflops": None}
+    if fl:  # the whole build: every profiled kernel's FP64 work over its wall time
+        flops = sum((measured_fp64_flops(k) or 0.0) * pw[k][0] for k in pw)
+        out["roofline"]["build_fp64_tflops"] = flops / t_warm / 1e12
 
     # 3. plain per-node build on every plain_stride-th node (timing sample)
     pick = np.arange(0, n, args.plain_stride)
