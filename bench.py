@@ -129,6 +129,11 @@ def parse():
                    help="complex2d: nodes in the CPU oracle's cache-build sample")
     p.add_argument("--kmeans", type=int, nargs="*", default=[],
                    help="complex2d: also trace k-means class caches with these K")
+    p.add_argument("--shots-buckets", type=float, nargs="*", default=[],
+                   help="shots: also time the eager batch with these tile ordering widths")
+    p.add_argument("--shots-frontier", type=float, nargs="*", default=[],
+                   help="shots: also time the eager batch on the node frontier with these "
+                        "bucket widths")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run 4 device-to-device copies of MIB MiB (HBM counter scale)")
     return p.parse_args()
@@ -656,6 +661,27 @@ def run_shots(args):
     shots = 2 * sum(len(m.sources) for m in models)
     res["eager"] = {"s": t_eager, "shots_per_s": shots / t_eager,
                     "star_edges_per_s_tau_fields": E_total / t_eager, "stats": stats.as_dict()}
+    for bw in args.shots_buckets:
+        st_b = C.TraceStats()
+        ob = C.trace_opts(outs, opts.tile_x, opts.tile_z, push_group=opts.push_group,
+                          launch=opts.launch if opts.launch != C.LAUNCH_FRONTIER else 0,
+                          bucket_width=bw, stats=st_b)
+        ev = _events(torch, stream)
+        C.chert_trace_batch(b, ob, ws, stream=stream)
+        t_b = _elapsed(torch, ev, stream)
+        res.setdefault("eager_ordered", {})[str(bw)] = {"s": t_b, "shots_per_s": shots / t_b,
+                                                        "stats": st_b.as_dict()}
+    for bw in args.shots_frontier:
+        st_b = C.TraceStats()
+        ob = C.trace_opts(outs, launch=C.LAUNCH_FRONTIER, bucket_width=bw, stats=st_b)
+        wsf = torch.empty(C.chert_trace_batch_workspace_bytes(b, ob), dtype=torch.uint8,
+                          device=dev)
+        ev = _events(torch, stream)
+        C.chert_trace_batch(b, ob, wsf, stream=stream)
+        t_b = _elapsed(torch, ev, stream)
+        del wsf
+        res.setdefault("eager_frontier", {})[str(bw)] = {"s": t_b, "shots_per_s": shots / t_b,
+                                                         "stats": st_b.as_dict()}
     # one persistent graph of the whole batch, replayed
     gopts = C.trace_opts(outs, opts.tile_x, opts.tile_z, push_group=opts.push_group,
                          launch=C.LAUNCH_PERSISTENT)

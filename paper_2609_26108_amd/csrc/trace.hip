@@ -48,6 +48,10 @@ constexpr size_t kWLdsBytes = 48 * 1024;  // class-pair table staged in LDS up t
 constexpr int kFlagActive = 1;  // a neighbour changed nodes in our halo
 constexpr int kFlagFull = 2;    // pull every interior node (iteration cap hit)
 constexpr int kFlagSeed = 4;    // first visit of the source tile: push the source
+// bits kSideShift + s, s = (sz + 1) * 3 + (sx + 1): the halo part facing the
+// neighbour at (sx, sz) changed, so the nodes within R of that side re-pull
+constexpr int kSideShift = 3;
+constexpr int kPullChunk = 8;  // per-node pulls: weight loads issued together
 // LDS class ids of halo cells carry this bit (push targets must be interior)
 constexpr int32_t kHaloBit = 0x40000000;
 constexpr int32_t kClassMask = 0x3fffffff;
@@ -353,7 +357,9 @@ __device__ __forceinline__ void activate(const RelaxArgs& a, int round, const Ti
     int nx_ = c.tx + dx, nz_ = c.tz + dz;
     if (nx_ < 0 || nx_ >= jb.ntx || nz_ < 0 || nz_ >= jb.ntz) continue;
     int32_t* f = &fout[pr.tile_base + nz_ * jb.ntx + nx_];
-    const int32_t bits = (bit == 4) ? (kFlagActive | kFlagFull) : kFlagActive;
+    // the neighbour's halo facing us, i.e. its side (-dx, -dz), changed
+    const int32_t bits =
+        (bit == 4) ? (kFlagActive | kFlagFull) : (kFlagActive | (1 << (kSideShift + 8 - bit)));
     if (a.bucket > 0.0)
       atomicMin(&a.key[(int64_t)((round + 1) & 1) * a.n_tiles + pr.tile_base + nz_ * jb.ntx + nx_],
                 key);
@@ -458,20 +464,17 @@ __device__ __forceinline__ void frontier_add(bool flag, int node, int32_t* list,
 
 
 
-// Does this visit pull node ml (LDS index)?  Border band, or all on kFlagFull.
+// Does this visit pull node ml (LDS index)?  The R-wide strips facing the
+// neighbours whose halo part changed (side bits), or all on kFlagFull.
 __device__ __forceinline__ bool pulls(const RelaxArgs& a, const TileCtx& c, int ml) {
   if (c.active & kFlagFull) return true;
   const int x = ml % a.lw - a.R, z = ml / a.lw - a.R;
-  return x < a.R || x >= a.tx - a.R || z < a.R || z >= a.tz - a.R;
-}
-
-// Number of nodes pulls() selects in this tile (for the work counters).
-__device__ __forceinline__ long long pull_count(const RelaxArgs& a, const TileCtx& c) {
-  const long long all = (long long)c.txe * c.tze;
-  if (c.active & kFlagFull) return all;
-  const int ix = max(0, min(c.txe, a.tx - a.R) - a.R);
-  const int iz = max(0, min(c.tze, a.tz - a.R) - a.R);
-  return all - (long long)ix * iz;
+  const bool near[2][3] = {{x < a.R, true, x >= a.tx - a.R}, {z < a.R, true, z >= a.tz - a.R}};
+  const int sides = (c.active >> kSideShift) & 0x1ff;
+  for (int sz = 0; sz < 3; ++sz)
+    for (int sx = 0; sx < 3; ++sx)
+      if (((sides >> (sz * 3 + sx)) & 1) && near[0][sx] && near[1][sz]) return true;
+  return false;
 }
 
 // LDS index of the problem's source if this visit seeds it, else -1.
@@ -507,6 +510,7 @@ __device__ __forceinline__ void relax_tau(const RelaxArgs& a, int round, int T) 
   extern __shared__ double smem_d[];
   __shared__ int s_flag, s_prob, s_mask, s_cnt[3];
   __shared__ unsigned long long s_key;
+  __shared__ int s_npull;
   const TileCtx c = tile_begin(a, round, T, &s_flag, &s_prob, 0);
   if (!c.active) return;
   const Smem s = carve(a, smem_d);
@@ -516,6 +520,7 @@ __device__ __forceinline__ void relax_tau(const RelaxArgs& a, int round, int T) 
   if (threadIdx.x == 0) {
     s_mask = 0;
     s_key = kInfBits;
+    s_npull = 0;
     s_cnt[0] = 0;
     s_cnt[1] = 0;
     s_cnt[2] = 0;
@@ -529,25 +534,45 @@ __device__ __forceinline__ void relax_tau(const RelaxArgs& a, int round, int T) 
   const double* Wp = stage_w(a, jb, pr.field, s);
   __syncthreads();
   const int ml = my_node(a, c);
-  long long raw = pull_count(a, c) * n_off;
+  long long raw = 0;
   const double orig = ml >= 0 ? s.val[ml] : 0.0;
 
   // pull over the border band (or every node), then seed the source
   {
     bool improved = false;
     if (ml >= 0 && pulls(a, c, ml)) {
+      atomicAdd(&s_npull, 1);
       const int kj = s.cls[ml];
       if (kj >= 0) {
         const int64_t gml = gnode(a, c, jb, ml);
         const double cur = s.val[ml];
         double best = cur;
-        for (int o = 0; o < n_off; ++o) {
-          const int ii = ml - s.off[o];
-          const int ki = s.cls[ii];
-          if (ki < 0) continue;
-          const double cand = __dadd_rn(
-              s.val[ii], w_pull(jb, Wp, pr.field, ki & kClassMask, kj, o, n_off, gml));
-          if (cand < best) best = cand;
+        if (jb.per_node) {
+          // the node's weight row from HBM, kPullChunk loads in flight at a time
+          const double* wrow = jb.W + ((int64_t)pr.field * jb.nx * jb.nz + gml) * n_off;
+          for (int o0 = 0; o0 < n_off; o0 += kPullChunk) {
+            double wv[kPullChunk];
+#pragma unroll
+            for (int u = 0; u < kPullChunk; ++u) wv[u] = o0 + u < n_off ? wrow[o0 + u] : 0.0;
+#pragma unroll
+            for (int u = 0; u < kPullChunk; ++u) {
+              const int o = o0 + u;
+              if (o >= n_off) break;
+              const int ii = ml - s.off[o];
+              if (s.cls[ii] < 0) continue;
+              const double cand = __dadd_rn(s.val[ii], wv[u]);
+              if (cand < best) best = cand;
+            }
+          }
+        } else {
+          for (int o = 0; o < n_off; ++o) {
+            const int ii = ml - s.off[o];
+            const int ki = s.cls[ii];
+            if (ki < 0) continue;
+            const double cand = __dadd_rn(
+                s.val[ii], w_pull(jb, Wp, pr.field, ki & kClassMask, kj, o, n_off, gml));
+            if (cand < best) best = cand;
+          }
         }
         if (best < cur) {
           s.val[ml] = best;
@@ -632,7 +657,7 @@ __device__ __forceinline__ void relax_tau(const RelaxArgs& a, int round, int T) 
     mask |= bb;
     if (bb && a.bucket > 0.0) atomicMin(&s_key, dbits(s.val[ml]));
   }
-  count_visit(a, 0, raw, it - 1);
+  count_visit(a, 0, raw + (long long)s_npull * n_off, it - 1);
   if (mask) atomicOr(&s_mask, mask);
   __syncthreads();
   if (threadIdx.x == 0 && s_mask) activate(a, round, c, pr, jb, s_mask, s_key);
@@ -644,6 +669,7 @@ __device__ __forceinline__ void relax_hop(const RelaxArgs& a, int round, int T) 
   extern __shared__ double smem_d[];
   __shared__ int s_flag, s_prob, s_mask, s_cnt[3];
   __shared__ unsigned long long s_key;
+  __shared__ int s_npull;
   const TileCtx c = tile_begin(a, round, T, &s_flag, &s_prob, 1);
   if (!c.active) return;
   const Smem s = carve(a, smem_d);
@@ -653,6 +679,7 @@ __device__ __forceinline__ void relax_hop(const RelaxArgs& a, int round, int T) 
   if (threadIdx.x == 0) {
     s_mask = 0;
     s_key = kInfBits;
+    s_npull = 0;
     s_cnt[0] = 0;
     s_cnt[1] = 0;
     s_cnt[2] = 0;
@@ -668,26 +695,45 @@ __device__ __forceinline__ void relax_hop(const RelaxArgs& a, int round, int T) 
   const double* Wp = stage_w(a, jb, pr.field, s);
   __syncthreads();
   const int ml = my_node(a, c);
-  long long raw = pull_count(a, c) * n_off;
+  long long raw = 0;
   const int32_t orig = ml >= 0 ? s.ival[ml] : 0;
 
   {
     bool improved = false;
     if (ml >= 0 && pulls(a, c, ml)) {
+      atomicAdd(&s_npull, 1);
       const int kj = s.cls[ml];
       const double tj = s.val[ml];
       if (kj >= 0 && tj < INFINITY) {
         const int64_t gml = gnode(a, c, jb, ml);
         const int32_t cur = s.ival[ml];
         int32_t best = cur;
-        for (int o = 0; o < n_off; ++o) {
-          const int ii = ml - s.off[o];
-          const int ki = s.cls[ii];
-          const int32_t hi = s.ival[ii];
-          if (ki < 0 || hi == kHopUnset || hi + 1 >= best) continue;
-          if (__dadd_rn(s.val[ii],
-                        w_pull(jb, Wp, pr.field, ki & kClassMask, kj, o, n_off, gml)) == tj)
-            best = hi + 1;
+        if (jb.per_node) {
+          const double* wrow = jb.W + ((int64_t)pr.field * jb.nx * jb.nz + gml) * n_off;
+          for (int o0 = 0; o0 < n_off; o0 += kPullChunk) {
+            double wv[kPullChunk];
+#pragma unroll
+            for (int u = 0; u < kPullChunk; ++u) wv[u] = o0 + u < n_off ? wrow[o0 + u] : 0.0;
+#pragma unroll
+            for (int u = 0; u < kPullChunk; ++u) {
+              const int o = o0 + u;
+              if (o >= n_off) break;
+              const int ii = ml - s.off[o];
+              const int32_t hi = s.ival[ii];
+              if (s.cls[ii] < 0 || hi == kHopUnset || hi + 1 >= best) continue;
+              if (__dadd_rn(s.val[ii], wv[u]) == tj) best = hi + 1;
+            }
+          }
+        } else {
+          for (int o = 0; o < n_off; ++o) {
+            const int ii = ml - s.off[o];
+            const int ki = s.cls[ii];
+            const int32_t hi = s.ival[ii];
+            if (ki < 0 || hi == kHopUnset || hi + 1 >= best) continue;
+            if (__dadd_rn(s.val[ii],
+                          w_pull(jb, Wp, pr.field, ki & kClassMask, kj, o, n_off, gml)) == tj)
+              best = hi + 1;
+          }
         }
         if (best < cur) {
           s.ival[ml] = best;
@@ -771,7 +817,7 @@ __device__ __forceinline__ void relax_hop(const RelaxArgs& a, int round, int T) 
     mask |= bb;
     if (bb && a.bucket > 0.0) atomicMin(&s_key, dbits((double)s.ival[ml]));
   }
-  count_visit(a, 1, raw, it - 1);
+  count_visit(a, 1, raw + (long long)s_npull * n_off, it - 1);
   if (mask) atomicOr(&s_mask, mask);
   __syncthreads();
   if (threadIdx.x == 0 && s_mask) activate(a, round, c, pr, jb, s_mask, s_key);
@@ -840,6 +886,7 @@ __device__ __forceinline__ void relax_tstar(const RelaxArgs& a, int round, int T
   extern __shared__ double smem_d[];
   __shared__ int s_flag, s_prob, s_mask, s_cnt[3];
   __shared__ unsigned long long s_key;
+  __shared__ int s_npull;
   const TileCtx c = tile_begin(a, round, T, &s_flag, &s_prob, 2);
   if (!c.active) return;
   const Smem s = carve(a, smem_d);
@@ -850,6 +897,7 @@ __device__ __forceinline__ void relax_tstar(const RelaxArgs& a, int round, int T
   if (threadIdx.x == 0) {
     s_mask = 0;
     s_key = kInfBits;
+    s_npull = 0;
     s_cnt[0] = 0;
     s_cnt[1] = 0;
     s_cnt[2] = 0;
@@ -867,11 +915,12 @@ __device__ __forceinline__ void relax_tstar(const RelaxArgs& a, int round, int T
   const double* WI = stage_w(a, jb, kFieldI, s);
   __syncthreads();
   const int ml = my_node(a, c);
-  long long raw = pull_count(a, c);
+  long long raw = 0;
 
   {
     bool known = false;
     if (ml >= 0 && pulls(a, c, ml)) {
+      atomicAdd(&s_npull, 1);
       const int o = s.ival[ml];
       if (o >= 0 && isnan(s.val[ml])) {
         const int ii = ml - s.off[o];
@@ -956,7 +1005,7 @@ __device__ __forceinline__ void relax_tstar(const RelaxArgs& a, int round, int T
       if (bb && a.bucket > 0.0) atomicMin(&s_key, dbits(s.val[ml]));
     }
   }
-  count_visit(a, 2, raw, it - 1);
+  count_visit(a, 2, raw + s_npull, it - 1);
   if (mask) atomicOr(&s_mask, mask);
   __syncthreads();
   if (threadIdx.x == 0 && s_mask) activate(a, round, c, pr, jb, s_mask, s_key);
@@ -1702,7 +1751,8 @@ const int kTuneLaunch[] = {CHERT_LAUNCH_PER_ROUND, CHERT_LAUNCH_PERSISTENT};
 }  // namespace
 
 const double kTuneBuckets[] = {0.0, 4.0, 16.0, 32.0, 64.0, 128.0, 256.0};
-const double kTuneBuckets2D[] = {0.0, 16.0, 64.0};  // 2D: the tiles usually win
+const double kTuneBuckets2D[] = {16.0, 64.0};  // 2D: the tiles usually win; one bucket
+                                               // can blow up on per-node media
 const double kTuneTileBuckets[] = {16.0, 64.0, 256.0};
 
 extern "C" size_t chert_trace_autotune_workspace_bytes(const chert_trace_job* jobs,
