@@ -332,7 +332,7 @@ int chert_trace_batch(const chert_trace_job *jobs, int32_t n_jobs,
  * fields); only the time does.  Candidates: in 3D the frontier iteration
  * with bucket widths 0 (one bucket), 4, 16, 32, 64, 128, 256 (units of the
  * smallest edge weight); in 2D the frontier with widths 16 and 64 and the
- * tiles 32x32, 64x16, 16x64, 32x16, 16x32, 128x8 with push groups 1, 2, 4,
+ * tiles 32x32, 64x16, 16x64, 32x16, 16x32, 128x8, 16x16 with push groups 1, 2, 4,
  * per-round and persistent launch, then, if tiles win, their ordering width
  * 16, 64 or 256 on the fastest shape.  Each is timed (HIP events,
  * second of two runs) on a probe batch made of the first source of every

@@ -37,6 +37,8 @@
 namespace chert {
 
 constexpr int kRelaxThreads = 1024;  // one node per thread: tiles <= 1024 nodes
+// threads of a tile workgroup: the tile's nodes rounded up to whole wavefronts
+static inline int tile_threads(int tx, int tz) { return (tx * tz + 63) / 64 * 64; }
 constexpr int kLocalIterCap = 4096;
 constexpr int32_t kHopUnset = 0x7fffffff;
 constexpr int kFieldR = 0, kFieldI = 1;
@@ -595,7 +597,8 @@ __device__ __forceinline__ void relax_tau(const RelaxArgs& a, int round, int T) 
   int ci = 0, it = 1;
   int nf = s_cnt[0];
   const int ngroups = (n_off + G - 1) / G;
-  const int q_step = kRelaxThreads / ngroups, r_step = kRelaxThreads % ngroups;
+  const int nt = blockDim.x;
+  const int q_step = nt / ngroups, r_step = nt % ngroups;
   while (nf > 0 && it <= kLocalIterCap) {
     const int cn = ci == 2 ? 0 : ci + 1, cz = cn == 2 ? 0 : cn + 1;
     int32_t* const lcur = (it & 1) ? s.l0 : s.l1;
@@ -605,9 +608,9 @@ __device__ __forceinline__ void relax_tau(const RelaxArgs& a, int round, int T) 
     // work items = (frontier node, group of G offsets), spread over the block;
     // every thread runs the same trip count so frontier_add sees whole waves
     const int total = nf * ngroups;
-    const int bound = (total + kRelaxThreads - 1) / kRelaxThreads * kRelaxThreads;
+    const int bound = (total + nt - 1) / nt * nt;
     int f = threadIdx.x / ngroups, g = threadIdx.x % ngroups;
-    for (int item = threadIdx.x; item < bound; item += kRelaxThreads) {
+    for (int item = threadIdx.x; item < bound; item += nt) {
       const bool live = item < total;
       const int i = live ? lcur[f] : 0;
 #pragma unroll
@@ -754,7 +757,8 @@ __device__ __forceinline__ void relax_hop(const RelaxArgs& a, int round, int T) 
   int ci = 0, it = 1;
   int nf = s_cnt[0];
   const int ngroups = (n_off + G - 1) / G;
-  const int q_step = kRelaxThreads / ngroups, r_step = kRelaxThreads % ngroups;
+  const int nt = blockDim.x;
+  const int q_step = nt / ngroups, r_step = nt % ngroups;
   while (nf > 0 && it <= kLocalIterCap) {
     const int cn = ci == 2 ? 0 : ci + 1, cz = cn == 2 ? 0 : cn + 1;
     int32_t* const lcur = (it & 1) ? s.l0 : s.l1;
@@ -764,9 +768,9 @@ __device__ __forceinline__ void relax_hop(const RelaxArgs& a, int round, int T) 
     // work items = (frontier node, group of G offsets), spread over the block;
     // every thread runs the same trip count so frontier_add sees whole waves
     const int total = nf * ngroups;
-    const int bound = (total + kRelaxThreads - 1) / kRelaxThreads * kRelaxThreads;
+    const int bound = (total + nt - 1) / nt * nt;
     int f = threadIdx.x / ngroups, g = threadIdx.x % ngroups;
-    for (int item = threadIdx.x; item < bound; item += kRelaxThreads) {
+    for (int item = threadIdx.x; item < bound; item += nt) {
       const bool live = item < total;
       const int i = live ? lcur[f] : 0;
 #pragma unroll
@@ -944,7 +948,8 @@ __device__ __forceinline__ void relax_tstar(const RelaxArgs& a, int round, int T
   int ci = 0, it = 1;
   int nf = s_cnt[0];
   const int ngroups = (n_off + G - 1) / G;
-  const int q_step = kRelaxThreads / ngroups, r_step = kRelaxThreads % ngroups;
+  const int nt = blockDim.x;
+  const int q_step = nt / ngroups, r_step = nt % ngroups;
   while (nf > 0 && it <= kLocalIterCap) {
     const int cn = ci == 2 ? 0 : ci + 1, cz = cn == 2 ? 0 : cn + 1;
     int32_t* const lcur = (it & 1) ? s.l0 : s.l1;
@@ -954,9 +959,9 @@ __device__ __forceinline__ void relax_tstar(const RelaxArgs& a, int round, int T
     // work items = (frontier node, group of G offsets), spread over the block;
     // every thread runs the same trip count so frontier_add sees whole waves
     const int total = nf * ngroups;
-    const int bound = (total + kRelaxThreads - 1) / kRelaxThreads * kRelaxThreads;
+    const int bound = (total + nt - 1) / nt * nt;
     int f = threadIdx.x / ngroups, g = threadIdx.x % ngroups;
-    for (int item = threadIdx.x; item < bound; item += kRelaxThreads) {
+    for (int item = threadIdx.x; item < bound; item += nt) {
       const bool live = item < total;
       const int i = live ? lcur[f] : 0;
 #pragma unroll
@@ -1312,7 +1317,8 @@ static int run_rounds(hipStream_t s, const RelaxArgs& a, void (*kern)(RelaxArgs,
     int nb = batch;
     if (r + nb > max_rounds) nb = max_rounds - r;
     for (int q = 0; q < nb; ++q)
-      CHERT_LAUNCH(name, kern, dim3((unsigned)grid), dim3(kRelaxThreads), lds, s, a, r + q);
+      CHERT_LAUNCH(name, kern, dim3((unsigned)grid), dim3((unsigned)tile_threads(a.tx, a.tz)), lds,
+                   s, a, r + q);
     hipError_t e = hipMemcpyAsync(counts, a.counter + r + 1, sizeof(int32_t) * nb,
                                   hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1346,12 +1352,12 @@ static PersistKern persist_kernel(int ph, int G) {
 
 // Persistent-launch grid: as many workgroups as the device holds at once
 // (never more than the tiles), so every workgroup of the launch is resident.
-static int persist_grid(const void* kern, size_t lds, int64_t n_tiles, int* grid) {
+static int persist_grid(const void* kern, int threads, size_t lds, int64_t n_tiles, int* grid) {
   int per_cu = 0, cus = 0, dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kRelaxThreads, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds);
   if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
   if (per_cu < 1) return fail(CHERT_ERR_HIP, "relaxation kernel does not fit on a compute unit");
   int64_t g = (int64_t)per_cu * cus;
@@ -1512,9 +1518,11 @@ static int prepare(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
   const int G = o->push_group ? o->push_group : 2;
   for (int ph = 0; ph < 3; ++ph) {
     if (o->launch == CHERT_LAUNCH_PERSISTENT)
-      rc = persist_grid((const void*)persist_kernel(ph, G), Q->lds, P.n_tiles, &Q->pgrid[ph]);
+      rc = persist_grid((const void*)persist_kernel(ph, G), tile_threads(P.tx, P.tz), Q->lds,
+                        P.n_tiles, &Q->pgrid[ph]);
     else
-      rc = persist_grid((const void*)round_kernel(ph, G), Q->lds, P.n_tiles, &Q->rgrid[ph]);
+      rc = persist_grid((const void*)round_kernel(ph, G), tile_threads(P.tx, P.tz), Q->lds,
+                        P.n_tiles, &Q->rgrid[ph]);
     if (rc) return rc;
     // per-round launches: one workgroup per tile while that is at most 4x
     // the resident workgroups (tile affinity), else 4x the resident
@@ -1593,7 +1601,7 @@ static int enqueue(const Prepared& Q, const chert_trace_job* jobs, int n_jobs,
     init_flags(ph == 2 ? 1 : 0);
     if (o->launch == CHERT_LAUNCH_PERSISTENT) {
       CHERT_LAUNCH(pname[ph], persist_kernel(ph, G), dim3((unsigned)Q.pgrid[ph]),
-                   dim3(kRelaxThreads), lds, s, a, pa);
+                   dim3((unsigned)tile_threads(a.tx, a.tz)), lds, s, a, pa);
       rounds[ph] = 0;  // read back by finish()
       return CHERT_OK;
     }
@@ -1745,7 +1753,7 @@ extern "C" int chert_trace_field(const chert_cache_desc* d, const void* cache_de
 // ------------------------------------------------------------- autotune --
 
 namespace {
-const int kTuneTiles[][2] = {{32, 32}, {64, 16}, {16, 64}, {32, 16}, {16, 32}, {128, 8}};
+const int kTuneTiles[][2] = {{32, 32}, {64, 16}, {16, 64}, {32, 16}, {16, 32}, {128, 8}, {16, 16}};
 const int kTuneGroups[] = {1, 2, 4};
 const int kTuneLaunch[] = {CHERT_LAUNCH_PER_ROUND, CHERT_LAUNCH_PERSISTENT};
 }  // namespace
