@@ -682,22 +682,33 @@ def run_shots(args):
         del wsf
         res.setdefault("eager_frontier", {})[str(bw)] = {"s": t_b, "shots_per_s": shots / t_b,
                                                          "stats": st_b.as_dict()}
-    # one persistent graph of the whole batch, replayed
-    gopts = C.trace_opts(outs, opts.tile_x, opts.tile_z, push_group=opts.push_group,
-                         launch=C.LAUNCH_PERSISTENT)
-    gs = torch.cuda.Stream()
-    torch.cuda.synchronize()
-    with torch.cuda.stream(gs):
-        graph = C.TraceGraph(b, gopts, ws, stream=gs)
-        graph.launch(gs)
-        graph.finish(None, gs)
-        ev = _events(torch, gs)
-        graph.launch(gs)
-        t_graph = _elapsed(torch, ev, gs)
-        st = C.TraceStats()
-        graph.finish(st, gs)
-    graph.close()
-    res["graph"] = {"s": t_graph, "shots_per_s": shots / t_graph, "rounds": list(st.rounds)}
+    # the whole batch as one graph, replayed: persistent phases, and
+    # per-round launches with a round budget from the eager run
+    def graph_time(gopts):
+        gs = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(gs):
+            graph = C.TraceGraph(b, gopts, ws, stream=gs)
+            graph.launch(gs)
+            graph.finish(None, gs)
+            ev = _events(torch, gs)
+            graph.launch(gs)
+            t_g = _elapsed(torch, ev, gs)
+            st = C.TraceStats()
+            graph.finish(st, gs)
+        graph.close()
+        return {"s": t_g, "shots_per_s": shots / t_g, "rounds": list(st.rounds)}
+    res["graph"] = graph_time(C.trace_opts(outs, opts.tile_x, opts.tile_z,
+                                           push_group=opts.push_group,
+                                           launch=C.LAUNCH_PERSISTENT,
+                                           bucket_width=opts.bucket_width))
+    budget = max(stats.rounds) + 16
+    res["graph_rounds"] = graph_time(C.trace_opts(outs, opts.tile_x, opts.tile_z,
+                                                  push_group=opts.push_group,
+                                                  launch=C.LAUNCH_PER_ROUND,
+                                                  bucket_width=opts.bucket_width,
+                                                  max_rounds=budget))
+    res["graph_rounds"]["round_budget"] = budget
     # surrogate form vs plain form: one shot per grid and mode traced on the
     # plain cache with chert_trace_field, against the batch (warm cache)
     worst = 0.0
@@ -715,8 +726,10 @@ def run_shots(args):
             worst = max(worst, r["max"])
         del w1
     res["tau_R_rel_surrogate_vs_plain_max"] = worst
-    res["value"] = res["graph"]["shots_per_s"]
-    res["unit"] = "shots/s ((source, mode) fields with tau_R + pred + t*, one graph replay)"
+    best = max(("graph", "graph_rounds"), key=lambda k: res[k]["shots_per_s"])
+    res["value"] = res[best]["shots_per_s"]
+    res["unit"] = ("shots/s ((source, mode) fields with tau_R + pred + t*, one graph replay: "
+                   + ("persistent phases)" if best == "graph" else "per-round launches)"))
     res["higher_is_better"] = True
     print(json.dumps(res))
 

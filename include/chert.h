@@ -348,14 +348,20 @@ int chert_trace_autotune(const chert_trace_job *jobs, int32_t n_jobs,
                          chert_trace_opts *o, void *workspace_dev,
                          size_t workspace_bytes, void *stream, double *best_ms);
 
-/* The whole of a chert_trace_batch call as one replayable HIP graph
- * (persistent launch only): create plans the batch, uploads its tables into
- * workspace_dev (synchronously on `stream`, which must not be NULL) and
- * captures every kernel -- edge weights, field initialisation, the three
- * persistent relaxation phases, predecessors and t* -- from stream capture
- * of `stream`.  launch enqueues one replay (asynchronous, no host work);
- * finish waits on `stream` and reports that replay's errors and counters
- * like chert_trace_batch; destroy releases the graph.  Outputs, caches and
+/* The whole of a chert_trace_batch call as one replayable HIP graph:
+ * create plans the batch, uploads its tables into workspace_dev
+ * (synchronously on `stream`, which must not be NULL) and captures every
+ * kernel -- edge weights, field initialisation, the three relaxation
+ * phases, predecessors and t* -- from stream capture of `stream`.  The
+ * phases are either the persistent launches (CHERT_LAUNCH_PERSISTENT) or,
+ * with CHERT_LAUNCH_PER_ROUND and a round budget max_rounds > 0, exactly
+ * max_rounds per-round launches each (rounds after convergence find no
+ * active tile and leave at once; a budget too short makes finish return
+ * NO_CONVERGENCE -- take it from an eager run's stats with a margin).  The
+ * node-frontier launch cannot be captured (INVALID_ARG).  launch enqueues
+ * one replay (asynchronous, no host work); finish waits on `stream` and
+ * reports that replay's errors and counters like chert_trace_batch; destroy
+ * releases the graph.  Outputs, caches and
  * the workspace named at create time must stay allocated while the graph
  * exists; their contents may change between replays (e.g. a rebuilt cache).
  * One replay at a time per workspace. */
@@ -484,8 +490,9 @@ int chert_surrogate_infer(const void *blob_dev, const float *x_dev, int64_t n,
  * the windowed plain search), [4] Newton not converged, [5] slope of the
  * ray-angle map too small, [6] theta_I not the root nearest 0, [7] residual
  * or entry rejected, [8] sweep samples evaluated by windowed searches,
- * [9] jobs whose windowed search failed its guard or needed more than 512
- * sweep samples. */
+ * [9] jobs whose windowed search failed its guard, needed more than 512
+ * sweep samples or found no room for its brackets (those jobs are redone by
+ * the plain path). */
 enum { CHERT_WARM_NSTATS = 10 };
 
 /* Scratch needed by chert_build_cache_surrogate. */

@@ -542,7 +542,8 @@ def chert_trace_autotune(batch, opts, workspace_dev, stream=None):
 
 
 class TraceGraph:
-    """A chert_trace_batch captured as one HIP graph (persistent launch).
+    """A chert_trace_batch captured as one HIP graph (persistent phases, or
+    per-round launches with a round budget).
     Keeps the batch, options and workspace referenced while it lives."""
 
     def __init__(self, batch, opts, workspace_dev, stream=None):

@@ -252,13 +252,13 @@ struct WindowTable {
 // Refine the bracket starting at sweep sample j and fold the root into the
 // running first-arrival choice (largest ray velocity; ties to the smaller
 // |theta_R - psi*|).
-template <class T>
-__device__ __forceinline__ void refine_bracket(const SolveArgs& a, const Medium& m, int mode,
-                                               const T& tab, int j, double psi_star, bool el,
-                                               bool* found, bool* ill, Entry* best) {
+// The root of the bracket at sweep sample j and its ray quantities; false if
+// neither the Newton step nor the bisection converges.  *cand_ill: the
+// bracket's ray-angle slope is below kIllSlope.
+__device__ __forceinline__ bool bracket_root(const SolveArgs& a, const Medium& m, int mode, int j,
+                                             double2 sa, double2 sb, double psi_star, bool el,
+                                             Entry* cand, bool* cand_ill) {
   const double dth = kTwoPi / a.n_sweep;
-  double2 sa = tab.at(j);
-  double2 sb = tab.at(j + 1 == a.n_sweep ? 0 : j + 1);
   double fa = wrap_pi(sa.y - psi_star);
   double fb = wrap_pi(sb.y - psi_star);
   double ta = (j + 0.5) * dth;
@@ -266,17 +266,24 @@ __device__ __forceinline__ void refine_bracket(const SolveArgs& a, const Medium&
   double x, y;
   bool ok = newton_root(m, mode, a.kernel, psi_star, ta, tb, sa.x, sb.x, fa, fb, &x, &y);
   if (!ok) ok = bisect_root(m, mode, a.kernel, psi_star, ta, tb, fa, &x, &y);
-  if (!ok) return;
+  if (!ok) return false;
   if (x >= kTwoPi) x -= kTwoPi;
   if (x < 0.0) x += kTwoPi;
   Vel v = energy_velocity(m, mode, a.kernel, x, y);
-  Entry cand;
-  ray_quantities(v, &cand);
-  cand.thR = x;
-  cand.thI = y;
+  ray_quantities(v, cand);
+  cand->thR = x;
+  cand->thI = y;
   double h = el ? 0.0 : homog_residual(v);
-  cand.res = fmax(fabs(h), fabs(wrap_pi(ray_angle(v) - psi_star)));
-  bool cand_ill = fabs((fb - fa) / (tb - ta)) < kIllSlope;
+  cand->res = fmax(fabs(h), fabs(wrap_pi(ray_angle(v) - psi_star)));
+  *cand_ill = fabs((fb - fa) / (tb - ta)) < kIllSlope;
+  return true;
+}
+
+// Fold a root into the running first-arrival choice, brackets in scan
+// order: the first root, then a larger ray velocity; ties (kTieRel) go to
+// the smaller |theta_R - psi*|.
+__device__ __forceinline__ void fold_choice(const Entry& cand, bool cand_ill, double psi_star,
+                                            bool* found, bool* ill, Entry* best) {
   bool take;
   if (!*found) take = true;
   else if (cand.V > best->V * (1.0 + kTieRel)) take = true;
@@ -287,6 +294,31 @@ __device__ __forceinline__ void refine_bracket(const SolveArgs& a, const Medium&
     *ill = cand_ill;
     *found = true;
   }
+}
+
+__device__ __forceinline__ void refine_bracket_at(const SolveArgs& a, const Medium& m, int mode,
+                                                  int j, double2 sa, double2 sb, double psi_star,
+                                                  bool el, bool* found, bool* ill, Entry* best) {
+  Entry cand;
+  bool cand_ill;
+  if (bracket_root(a, m, mode, j, sa, sb, psi_star, el, &cand, &cand_ill))
+    fold_choice(cand, cand_ill, psi_star, found, ill, best);
+}
+
+template <class T>
+__device__ __forceinline__ void refine_bracket(const SolveArgs& a, const Medium& m, int mode,
+                                               const T& tab, int j, double psi_star, bool el,
+                                               bool* found, bool* ill, Entry* best) {
+  refine_bracket_at(a, m, mode, j, tab.at(j), tab.at(j + 1 == a.n_sweep ? 0 : j + 1), psi_star,
+                    el, found, ill, best);
+}
+
+// status of a solved direction from the folded choice (as the plain search)
+__device__ __forceinline__ int32_t solve_status(bool found, bool ill, const Entry& best) {
+  if (!found) return CHERT_ST_NO_BRACKET;
+  int32_t st = ill ? CHERT_ST_ILL : CHERT_ST_OK;
+  if (!(best.A >= 0.0) || !isfinite(best.V) || !(best.V > 0.0)) st |= CHERT_ST_NONPHYS;
+  return st;
 }
 
 template <class T>
@@ -332,10 +364,7 @@ __device__ __forceinline__ int32_t solve_dir(const SolveArgs& a, const Medium& m
       refine_bracket(a, m, mode, tab, j, psi_star, el, &found, &ill, best);
     }
   }
-  if (!found) return CHERT_ST_NO_BRACKET;
-  int32_t st = ill ? CHERT_ST_ILL : CHERT_ST_OK;
-  if (!(best->A >= 0.0) || !isfinite(best->V) || !(best->V > 0.0)) st |= CHERT_ST_NONPHYS;
-  return st;
+  return solve_status(found, ill, *best);
 }
 
 // Write the solved entry and its centrosymmetric copy (same ray quantities,
@@ -387,46 +416,102 @@ __device__ __forceinline__ int32_t class_block(const chert_class& c, int mode) {
 
 // Two-launch path (few classes): one workgroup per (mode, class, 64
 // directions), sweep table from k_sweep staged in LDS.
+// Class caches: SPLIT lanes per target direction, 64 / SPLIT directions per
+// workgroup (SPLIT = 4 when there are too few directions to fill the
+// device, else 1).  Each lane scans its share of the sweep table for
+// brackets and refines them; the direction's first lane then folds the
+// roots in scan order (the plain search's choice, exactly), or, if a share
+// held more than kSolveSlots brackets, runs the serial search itself.
+constexpr int kSolveSlots = 3;
+struct SolveCand {
+  Entry e;
+  int32_t ok, ill;
+};
+template <int SPLIT>
 __global__ void __launch_bounds__(64) k_solve(SolveArgs a) {
+  constexpr int kSolveSplit = SPLIT, kSolveDirs = 64 / SPLIT;
   extern __shared__ double2 tab[];
+  __shared__ SolveCand s_c[kSolveDirs][kSolveSplit * kSolveSlots];
+  __shared__ int s_nc[kSolveDirs][kSolveSplit];
+  __shared__ int s_over[kSolveDirs];
   __shared__ int s_br[64 * kMaxBr];
-  const int chunks = (a.n_solve + 63) / 64;
+  const int chunks = (a.n_solve + kSolveDirs - 1) / kSolveDirs;
   const int64_t job = blockIdx.x / chunks;
   const int chunk = blockIdx.x % chunks;
   const int64_t k = job % a.n_classes;
   const int mode = a.modes[job / a.n_classes];
   const double2* src = a.table + job * a.n_sweep;
   for (int j = threadIdx.x; j < a.n_sweep; j += blockDim.x) tab[j] = src[j];
+  const int dl = threadIdx.x / kSolveSplit, q = threadIdx.x % kSolveSplit;
+  if (q == 0) s_over[dl] = 0;
   __syncthreads();
 
-  const int sidx = chunk * 64 + threadIdx.x;
-  if (sidx >= a.n_solve) return;
+  const int sidx = chunk * kSolveDirs + dl;
+  const bool valid = sidx < a.n_solve;
   const int64_t row = ((int64_t)mode * a.n_classes + k) * a.n_cols;
   const chert_class c = a.classes[k];
+  const int32_t blocked = class_block(c, mode);
+  const Medium m = load_medium(c);
+  const FullTable full{tab, a.n_sweep};
+  double3 f = make_double3(0.0, 0.0, 0.0);
+  int d = 0, col = 0, pcol = 0;
+  double psi_star = 0.0;
+  if (valid) {
+    if (a.dim == 3) {
+      f = fib_dir(a, sidx);
+      psi_star = blocked ? 0.0 : polar_to_axis(f, c);
+    } else {
+      dir_cols(a, sidx, &d, &col, &pcol);
+      psi_star = blocked ? 0.0 : dir_psi(a, d, m.tilt);
+    }
+  }
+  const bool el = theta_i_zero(m, mode);
+  if (valid && !blocked) {
+    // this lane's share of the bracket scan, then its roots
+    const int span = (a.n_sweep + kSolveSplit - 1) / kSolveSplit;
+    const int lo = q * span, hi = min(a.n_sweep, lo + span);
+    int brj[kSolveSlots];
+    int nb = 0;
+    for (int j = lo; j < hi; ++j) {
+      if (!is_bracket(full, j, a.n_sweep, psi_star)) continue;
+      if (nb < kSolveSlots) brj[nb] = j;
+      ++nb;
+    }
+    if (nb > kSolveSlots) s_over[dl] = 1;
+    const int nk = nb < kSolveSlots ? nb : kSolveSlots;
+    for (int b = 0; b < nk; ++b) {
+      SolveCand& sc = s_c[dl][q * kSolveSlots + b];
+      bool ill = false;
+      const int j = brj[b];
+      sc.ok = bracket_root(a, m, mode, j, tab[j], tab[j + 1 == a.n_sweep ? 0 : j + 1], psi_star,
+                           el, &sc.e, &ill) ? 1 : 0;
+      sc.ill = ill ? 1 : 0;
+    }
+    s_nc[dl][q] = nk;
+  }
+  __syncthreads();
+  if (!valid || q != 0) return;
   Entry best{};
   best.V = NAN;
-  int32_t st = class_block(c, mode);
-  if (a.dim == 3) {
-    const double3 f = fib_dir(a, sidx);
-    const int64_t stride = 3 * a.n_classes * (int64_t)a.n_cols;
-    if (!st) {
-      const Medium m = load_medium(c);
-      st = solve_dir(a, m, mode, FullTable{tab, a.n_sweep}, polar_to_axis(f, c),
-                     s_br + threadIdx.x * kMaxBr, &best);
+  int32_t st = blocked;
+  if (!blocked) {
+    if (s_over[dl]) {
+      st = solve_dir(a, m, mode, full, psi_star, s_br + threadIdx.x * kMaxBr, &best);
+    } else {
+      bool found = false, ill = false;
+      for (int qq = 0; qq < kSolveSplit; ++qq)
+        for (int b = 0; b < s_nc[dl][qq]; ++b) {
+          const SolveCand& sc = s_c[dl][qq * kSolveSlots + b];
+          if (sc.ok) fold_choice(sc.e, sc.ill != 0, psi_star, &found, &ill, &best);
+        }
+      st = solve_status(found, ill, best);
     }
-    store_single(a, row + sidx, stride, best, f, st);
+  }
+  if (a.dim == 3) {
+    store_single(a, row + sidx, 3 * a.n_classes * (int64_t)a.n_cols, best, f, st);
     return;
   }
-  int d, col, pcol;
-  dir_cols(a, sidx, &d, &col, &pcol);
-  if (st) {
-    store_pair(a, row, col, pcol, best, 0.0, st);
-    return;
-  }
-  const Medium m = load_medium(c);
-  st = solve_dir(a, m, mode, FullTable{tab, a.n_sweep}, dir_psi(a, d, m.tilt),
-                 s_br + threadIdx.x * kMaxBr, &best);
-  store_pair(a, row, col, pcol, best, m.tilt, st);
+  store_pair(a, row, col, pcol, best, blocked ? 0.0 : m.tilt, st);
 }
 
 // Fused path (many classes, e.g. one per node): one workgroup per
@@ -494,6 +579,13 @@ constexpr int kFoldWords = (kFoldBins + 31) / 32;
 constexpr double kWarmSlope = 0.05;                 // accepted roots: slope at least this
 constexpr double kWarmWindow = 0.35;                // Newton may move theta_R this far [rad]
 
+// a bracket of a fold direction's windowed table: sweep sample j and the
+// (theta_I, ray angle) pairs at j and j + 1
+struct WinBracket {
+  double2 sa, sb;
+  int32_t j, pad[3];
+};
+
 struct WarmArgs {
   SolveArgs so;
   const void* blob;
@@ -502,6 +594,12 @@ struct WarmArgs {
   int32_t* fb_len;
   int32_t* win_list;            // jobs with directions near a fold (k_warm_window)
   int32_t* win_len;
+  int4* dirs;                   // fold directions: (job, sidx, first bracket, brackets)
+  int32_t* dir_len;
+  int64_t dir_cap;
+  WinBracket* brs;              // their brackets, in scan order per direction
+  int32_t* br_len;
+  int64_t br_cap;
   unsigned long long* stats;    // CHERT_WARM_NSTATS counters
   double resid_tol;
 };
@@ -794,6 +892,9 @@ __global__ void __launch_bounds__(64) k_warm_solve(WarmArgs w) {
 // kWinCap samples, the job goes to the plain path).  One wavefront per
 // listed job, grid-strided; the marked samples are kept compact in LDS.
 constexpr int kWinCap = 512;
+// room for fold directions and their brackets, per job on average (more: the
+// job is redone by the plain path)
+constexpr int64_t kDirsPerJob = 4, kBracketsPerJob = 8;
 __global__ void __launch_bounds__(64) k_warm_window(WarmArgs w) {
   extern __shared__ double2 s_ent[];  // [kWinCap] (theta_I, psi); then idx, pos
   int16_t* s_idx = reinterpret_cast<int16_t*>(s_ent + kWinCap);  // [kWinCap]
@@ -801,7 +902,6 @@ __global__ void __launch_bounds__(64) k_warm_window(WarmArgs w) {
   __shared__ uint32_t s_fold[kFoldWords];
   __shared__ uint32_t s_mask[kMaxSweep / 32];
   __shared__ int16_t s_flag[kMaxSubset / 2];
-  __shared__ int s_br[64 * kMaxBr];
   __shared__ int s_all, s_nflag, s_bad;
 
   const SolveArgs& a = w.so;
@@ -890,21 +990,54 @@ __global__ void __launch_bounds__(64) k_warm_window(WarmArgs w) {
     }
     samples += (unsigned long long)nl;
     __syncthreads();
-    if (s_bad) {
-      if (lane == 0) {
-        ++guard;
-        w.fb_list[atomicAdd(w.fb_len, 1)] = (int32_t)job;
-      }
-    } else {
+    if (!s_bad) {
+      // every bracket of every fold direction goes to the flat refinement
+      // (k_warm_fold): one record per direction, its brackets contiguous in
+      // scan order.  All lanes scan the table for one direction at a time.
       const WindowTable tab{s_pos, s_ent, s_idx, nl};
-      for (int f = lane; f < nflag; f += 64) {
+      for (int f = 0; f < nflag; ++f) {
         int d, col, pcol;
-        dir_cols(a, s_flag[f], &d, &col, &pcol);
-        Entry best{};
-        const int32_t st = solve_dir(a, m, mode, tab, dir_psi(a, d, m.tilt), s_br + lane * kMaxBr,
-                                     &best);
-        store_pair(a, row, col, pcol, best, m.tilt, st);
+        const int sidx = s_flag[f];
+        dir_cols(a, sidx, &d, &col, &pcol);
+        const double psi_star = dir_psi(a, d, m.tilt);
+        int nbr = 0;
+        for (int base = 0; base < nl; base += 64)
+          nbr += __popcll(__ballot(base + lane < nl &&
+                                   is_bracket(tab, s_idx[base + lane], a.n_sweep, psi_star)));
+        int rec = 0, first = 0;
+        if (lane == 0) {
+          rec = atomicAdd(w.dir_len, 1);
+          first = atomicAdd(w.br_len, nbr);
+        }
+        rec = __shfl(rec, 0);
+        first = __shfl(first, 0);
+        if (rec >= w.dir_cap || (int64_t)first + nbr > w.br_cap) {
+          if (lane == 0 && rec < w.dir_cap) w.dirs[rec] = make_int4(-1, 0, 0, 0);
+          s_bad = 1;  // no room: the job is redone below
+          break;      // wavefront-uniform
+        }
+        int q = first;
+        for (int base = 0; base < nl; base += 64) {
+          const bool br = base + lane < nl &&
+                          is_bracket(tab, s_idx[base + lane], a.n_sweep, psi_star);
+          const unsigned long long mask = __ballot(br);
+          if (br) {
+            const int jj = s_idx[base + lane];
+            WinBracket b;
+            b.sa = tab.at(jj);
+            b.sb = tab.at(jj + 1 == a.n_sweep ? 0 : jj + 1);
+            b.j = jj;
+            w.brs[q + __popcll(mask & ((1ull << lane) - 1ull))] = b;
+          }
+          q += __popcll(mask);
+        }
+        if (lane == 0) w.dirs[rec] = make_int4((int)job, sidx, first, nbr);
       }
+      __syncthreads();
+    }
+    if (s_bad && lane == 0) {  // guard failed or no room: the plain path redoes the job
+      ++guard;
+      w.fb_list[atomicAdd(w.fb_len, 1)] = (int32_t)job;
     }
   }
   if (lane == 0 && samples) atomicAdd(&w.stats[8], samples);
@@ -914,9 +1047,41 @@ __global__ void __launch_bounds__(64) k_warm_window(WarmArgs w) {
   }
 }
 
+// Fold directions across all window jobs, one lane each: refine the
+// direction's brackets in scan order and keep the plain search's choice
+// (the fold of refine_bracket), then store the entry and its copy.
+__global__ void __launch_bounds__(64) k_warm_fold(WarmArgs w) {
+  const SolveArgs& a = w.so;
+  const int64_t n = *w.dir_len < w.dir_cap ? *w.dir_len : w.dir_cap;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int4 r = w.dirs[t];
+    if (r.x < 0) continue;
+    const int64_t job = r.x;
+    const int64_t k = job % a.n_classes;
+    const int mode = a.modes[job / a.n_classes];
+    const chert_class c = a.classes[k];
+    const int64_t row = ((int64_t)mode * a.n_classes + k) * a.n_cols;
+    const Medium m = load_medium(c);
+    const bool el = theta_i_zero(m, mode);
+    int d, col, pcol;
+    dir_cols(a, r.y, &d, &col, &pcol);
+    const double psi_star = dir_psi(a, d, m.tilt);
+    bool found = false, ill = false;
+    Entry best{};
+    for (int b = 0; b < r.w; ++b) {
+      const WinBracket br = w.brs[r.z + b];
+      refine_bracket_at(a, m, mode, br.j, br.sa, br.sb, psi_star, el, &found, &ill, &best);
+    }
+    store_pair(a, row, col, pcol, best, m.tilt, solve_status(found, ill, best));
+  }
+}
+
 __global__ void k_warm_zero(int32_t* fb_len, int32_t* win_len, unsigned long long* stats) {
   if (threadIdx.x == 0) *fb_len = 0;
   if (threadIdx.x == 1) *win_len = 0;
+  if (threadIdx.x == 2) win_len[1] = 0;  // fold directions
+  if (threadIdx.x == 3) win_len[2] = 0;  // their brackets
   if (threadIdx.x < CHERT_WARM_NSTATS) stats[threadIdx.x] = 0ull;
 }
 
@@ -1054,10 +1219,17 @@ extern "C" int chert_build_cache(const chert_cache_desc* d, const chert_class* c
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     CHERT_LAUNCH("k_sweep", k_sweep, dim3((unsigned)blocks), dim3(256), 0, s, sa);
-    const int chunks = (so.n_solve + 63) / 64;
+    // few directions (latency bound): 4 lanes share each direction's scan
+    const bool split = jobs * ((so.n_solve + 63) / 64) < 1024;
+    const int per_wg = split ? 16 : 64;
+    const int64_t chunks = (so.n_solve + per_wg - 1) / per_wg;
     if (jobs * chunks > 0x7fffffffLL) return fail(CHERT_ERR_INVALID_ARG, "too many entries");
-    CHERT_LAUNCH("k_solve", k_solve, dim3((unsigned)(jobs * chunks)), dim3(64),
-                 (size_t)d->n_sweep * sizeof(double2), s, so);
+    if (split)
+      CHERT_LAUNCH("k_solve", k_solve<4>, dim3((unsigned)(jobs * chunks)), dim3(64),
+                   (size_t)d->n_sweep * sizeof(double2), s, so);
+    else
+      CHERT_LAUNCH("k_solve", k_solve<1>, dim3((unsigned)(jobs * chunks)), dim3(64),
+                   (size_t)d->n_sweep * sizeof(double2), s, so);
   }
   return launch_status();
 }
@@ -1072,7 +1244,8 @@ extern "C" size_t chert_build_cache_surrogate_workspace_bytes(const chert_cache_
   if (!d || n_classes <= 0 || chert_cache_layout_of(d, n_classes, &lay) != CHERT_OK) return 0;
   const SolveArgs so = solve_args(d, nullptr, n_classes, nullptr, lay, nullptr);
   const size_t jobs = (size_t)n_jobs_of(d, n_classes);
-  return al256(jobs * so.n_solve * sizeof(float2)) + 2 * al256(jobs * sizeof(int32_t)) + 256;
+  return al256(jobs * so.n_solve * sizeof(float2)) + 2 * al256(jobs * sizeof(int32_t)) + 256 +
+         al256(jobs * kDirsPerJob * sizeof(int4)) + al256(jobs * kBracketsPerJob * sizeof(WinBracket));
 }
 
 extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
@@ -1107,6 +1280,15 @@ extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
   w.win_list = (int32_t*)(ws + al256(rows * sizeof(float2)) + al256(jobs * sizeof(int32_t)));
   w.fb_len = (int32_t*)(ws + al256(rows * sizeof(float2)) + 2 * al256(jobs * sizeof(int32_t)));
   w.win_len = w.fb_len + 1;
+  w.dir_len = w.fb_len + 2;
+  w.br_len = w.fb_len + 3;
+  {
+    uint8_t* tail = ws + al256(rows * sizeof(float2)) + 2 * al256(jobs * sizeof(int32_t)) + 256;
+    w.dir_cap = jobs * kDirsPerJob;
+    w.dirs = (int4*)tail;
+    w.br_cap = jobs * kBracketsPerJob;
+    w.brs = (WinBracket*)(tail + al256(jobs * kDirsPerJob * sizeof(int4)));
+  }
   w.stats = stats_dev ? (unsigned long long*)stats_dev : (unsigned long long*)(w.fb_len + 16);
   w.resid_tol = resid_tol > 0.0 ? resid_tol : 1e-11;
 
@@ -1124,6 +1306,8 @@ extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
     CHERT_LAUNCH("k_warm_window", k_warm_window, dim3((unsigned)grid), dim3(64),
                  kWinCap * (sizeof(double2) + sizeof(int16_t)) +
                      (size_t)d->n_sweep * sizeof(int16_t), s, w);
+    const int64_t fgrid = (w.dir_cap + 63) / 64 < 8192 ? (w.dir_cap + 63) / 64 : 8192;
+    CHERT_LAUNCH("k_warm_fold", k_warm_fold, dim3((unsigned)fgrid), dim3(64), 0, s, w);
     CHERT_LAUNCH("k_build_fused", k_build_fused, dim3((unsigned)grid), dim3(kNodeThreads),
                  (size_t)d->n_sweep * sizeof(double2), s, w.so, (const int32_t*)w.fb_list,
                  (const int32_t*)w.fb_len, jobs);

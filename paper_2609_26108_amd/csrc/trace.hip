@@ -1134,6 +1134,19 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_persist(RelaxArgs a, Pe
   if (blockIdx.x == 0 && threadIdx.x == 0) p.result[PH] = -1;
 }
 
+// A phase run for a fixed number of per-round launches (graph capture):
+// rounds to convergence (the first round that activated nothing, + 1) or
+// -1 if the budget was too short.  One thread.
+__global__ void k_round_count(const int32_t* counter, int max_rounds, int32_t* result) {
+  int r = -1;
+  for (int q = 1; q <= max_rounds; ++q)
+    if (counter[q] == 0) {
+      r = q;
+      break;
+    }
+  *result = r;
+}
+
 // unreachable nodes: t* = +inf.  blockIdx.y = problem.
 __global__ void k_tstar_finish(const ProbDev* probs, const JobDev* jobs) {
   const ProbDev pr = probs[blockIdx.y];
@@ -1382,6 +1395,7 @@ struct Prepared {
   int32_t* dcol = nullptr;
   int pgrid[3] = {0, 0, 0};  // persistent-launch grid per phase
   int rgrid[3] = {0, 0, 0};  // per-round launch grid per phase
+  bool fixed_rounds = false;  // per-round launches without host checks (graphs)
 };
 
 // Plan the batch and upload its tables (synchronous on s).
@@ -1605,6 +1619,15 @@ static int enqueue(const Prepared& Q, const chert_trace_job* jobs, int n_jobs,
       rounds[ph] = 0;  // read back by finish()
       return CHERT_OK;
     }
+    if (Q.fixed_rounds) {  // every round of the budget, convergence read back by finish()
+      for (int r = 0; r < P.max_rounds; ++r)
+        CHERT_LAUNCH(kname[ph], round_kernel(ph, G), dim3((unsigned)Q.rgrid[ph]),
+                     dim3((unsigned)tile_threads(a.tx, a.tz)), lds, s, a, r);
+      CHERT_LAUNCH("k_round_count", k_round_count, dim3(1), dim3(1), 0, s, a.counter,
+                   P.max_rounds, pa.result + ph);
+      rounds[ph] = 0;
+      return CHERT_OK;
+    }
     return run_rounds(s, a, round_kernel(ph, G), kname[ph], Q.rgrid[ph], lds, P.max_rounds,
                       &rounds[ph]);
   };
@@ -1644,7 +1667,7 @@ static int finish(const Prepared& Q, const chert_trace_opts* o, hipStream_t s, i
   const bool ran[3] = {true, (outs & (CHERT_OUT_PRED_P | CHERT_OUT_PRED_A)) != 0,
                        (outs & CHERT_OUT_TSTAR) != 0};
   int status = CHERT_OK;
-  if (o->launch == CHERT_LAUNCH_PERSISTENT)
+  if (o->launch == CHERT_LAUNCH_PERSISTENT || Q.fixed_rounds)
     for (int ph = 0; ph < 3; ++ph) {
       rounds[ph] = ran[ph] ? hres[ph] : 0;
       if (ran[ph] && hres[ph] == -2 && !status)
@@ -1877,8 +1900,11 @@ extern "C" int chert_trace_graph_create(const chert_trace_job* jobs, int32_t n_j
                                         chert_trace_graph** out) {
   if (!out) return fail(CHERT_ERR_INVALID_ARG, "null graph handle");
   *out = nullptr;
-  if (!o || o->launch != CHERT_LAUNCH_PERSISTENT)
-    return fail(CHERT_ERR_INVALID_ARG, "graph capture needs the persistent launch");
+  if (!o || !(o->launch == CHERT_LAUNCH_PERSISTENT ||
+               (o->launch == CHERT_LAUNCH_PER_ROUND && o->max_rounds > 0)))
+    return fail(CHERT_ERR_INVALID_ARG,
+                "graph capture needs the persistent launch, or per-round launches with a "
+                "round budget (max_rounds > 0)");
   if (!stream) return fail(CHERT_ERR_INVALID_ARG, "graph capture needs a non-null stream");
   hipStream_t s = (hipStream_t)stream;
   chert_trace_graph* G = new (std::nothrow) chert_trace_graph();
@@ -1890,6 +1916,7 @@ extern "C" int chert_trace_graph_create(const chert_trace_job* jobs, int32_t n_j
   }
   G->o = *o;
   G->o.stats_host = nullptr;
+  G->Q.fixed_rounds = (o->launch == CHERT_LAUNCH_PER_ROUND);
   const bool prof = chert::prof_suspend();
   hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) {

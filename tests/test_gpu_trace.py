@@ -234,15 +234,26 @@ def test_batch_uneven_grids_modes_sources_bitwise(G, launch, bucket):
     check_batch(jobs)
 
 
-@pytest.mark.parametrize("bucket", [0.0, 16.0])
-def test_graph_replays_match_eager(G, bucket):
-    """The batch captured as one graph: three replays, each after eager work
-    of the program's own and a wipe of the outputs, equal the eager
-    persistent run bitwise (and so the oracle), with or without tile
+@pytest.mark.parametrize("launch,bucket", [(1, 0.0), (1, 16.0), (0, 0.0), (0, 16.0)])
+def test_graph_replays_match_eager(G, launch, bucket):
+    """The batch captured as one graph (persistent phases, or per-round
+    launches with a round budget from an eager run): three replays, each
+    after eager work of the program's own and a wipe of the outputs, equal
+    the eager run bitwise (and so the oracle), with or without tile
     ordering."""
     Cm = C()
     b, jobs, keep = uneven_batch(G)
-    opts = Cm.trace_opts(Cm.OUT_ALL, launch=Cm.LAUNCH_PERSISTENT, bucket_width=bucket)
+    budget = 0
+    if launch == Cm.LAUNCH_PER_ROUND:
+        st = Cm.TraceStats()
+        o0 = Cm.trace_opts(Cm.OUT_ALL, bucket_width=bucket, stats=st)
+        w0 = torch.empty(Cm.chert_trace_batch_workspace_bytes(b, o0), dtype=torch.uint8,
+                         device=G.DEV)
+        Cm.chert_trace_batch(b, o0, w0)
+        torch.cuda.synchronize()
+        budget = max(st.rounds) + 8
+        del w0
+    opts = Cm.trace_opts(Cm.OUT_ALL, launch=launch, bucket_width=bucket, max_rounds=budget)
     ws = torch.empty(Cm.chert_trace_batch_workspace_bytes(b, opts), dtype=torch.uint8,
                      device=G.DEV)
     Cm.chert_trace_batch(b, opts, ws)
@@ -271,6 +282,26 @@ def test_graph_replays_match_eager(G, bucket):
     finally:
         graph.close()
     check_batch(jobs)
+
+
+def test_graph_short_round_budget_reports_no_convergence(G):
+    """A per-round graph whose round budget is too short finishes with
+    NO_CONVERGENCE (every kernel still exits normally)."""
+    Cm = C()
+    b, jobs, keep = uneven_batch(G)
+    opts = Cm.trace_opts(Cm.OUT_ALL, launch=Cm.LAUNCH_PER_ROUND, max_rounds=2)
+    ws = torch.empty(Cm.chert_trace_batch_workspace_bytes(b, opts), dtype=torch.uint8,
+                     device=G.DEV)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        graph = Cm.TraceGraph(b, opts, ws, stream=stream)
+    try:
+        graph.launch(stream)
+        with pytest.raises(Cm.ChertError) as e:
+            graph.finish(Cm.TraceStats(), stream)
+        assert e.value.code == 4, e.value
+    finally:
+        graph.close()
 
 
 def test_autotuned_options_give_identical_fields(G):
