@@ -77,24 +77,7 @@ struct JobF {
                       // row j, offset o holds the edge j - o -> j
 };
 
-// Weight of the edge i -> j = i + o read from the tail's row.  Per node that
-// is row i at the reversed offset (the star is symmetric: index n_off-1-o is
-// -o), whose entry is the edge j -> i: equal bitwise, since the cache holds
-// direction d + n_dirs/2 as the exact copy of d and L_o is even in o.  False
-// when a class id is out of range.
-__device__ __forceinline__ bool w_tail(const JobF& J, int n_off, int field, int i, int j, int o,
-                                       double* w) {
-  if (J.per_node) {
-    *w = J.W[((int64_t)field * J.n + i) * n_off + (n_off - 1 - o)];
-    return true;
-  }
-  const int ci = J.cls[i], cj = J.cls[j];
-  if (ci < 0 || ci >= J.K || cj < 0 || cj >= J.K) return false;
-  *w = J.W[(((int64_t)field * J.K + ci) * J.K + cj) * n_off + o];
-  return true;
-}
-
-// The same edge read from the head's row.
+// Weight of the edge i -> j = i + o read on the head's side (per node: row j).
 __device__ __forceinline__ bool w_head(const JobF& J, int n_off, int field, int i, int j, int o,
                                        double* w) {
   if (J.per_node) {
@@ -265,51 +248,76 @@ __global__ void k_front_far_split(RF a, int epoch, int it) {
   }
 }
 
+// Weight of the edge i -> j = i + o read on the tail's side: class mode from
+// the tail's class ci; per node from row i at the reversed offset (the star
+// is symmetric: index n_off-1-o is -o), whose entry is the edge j -> i --
+// equal bitwise, since the cache holds direction d + n_dirs/2 as the exact
+// copy of d and L_o is even in o.  False when a class id is out of range.
+__device__ __forceinline__ bool w_out(const JobF& J, int n_off, int field, int i, int ci, int j,
+                                      int o, double* w) {
+  if (J.per_node) {
+    *w = J.W[((int64_t)field * J.n + i) * n_off + (n_off - 1 - o)];
+    return true;
+  }
+  const int cj = J.cls[j];
+  if (ci < 0 || ci >= J.K || cj < 0 || cj >= J.K) return false;
+  *w = J.W[(((int64_t)field * J.K + ci) * J.K + cj) * n_off + o];
+  return true;
+}
+
+// One wavefront per frontier item, its lanes over the star offsets: the
+// item is decoded once and its traveltime read once per wavefront.
 __global__ void __launch_bounds__(kFrontierThreads) k_front_relax(RF a, int it, int epoch) {
   const int n_near = a.counts[it];
   if (n_near == 0) return;
-  const int64_t total = (int64_t)n_near * a.n_off;
   const int64_t* lin = a.lists + (int64_t)(it & 1) * a.cap;
   int64_t* lout = a.lists + (int64_t)((it + 1) & 1) * a.cap;
+  int64_t* far = a.far + (int64_t)(epoch & 1) * a.cap;
+  const int lane = __lane_id();
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   long long raw = 0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
-    const int64_t t = base + threadIdx.x;
-    bool want = false, later = false;
-    int64_t out = 0;
-    if (t < total) {
-      ++raw;
-      const int64_t f = t / a.n_off;
-      const int o = (int)(t - f * a.n_off);
-      const int64_t item = lin[f];
-      const int p = (int)(item >> 32);
-      const int i = (int)(item & 0xffffffffLL);
-      const ProbF P = a.probs[p];
-      const JobF J = a.jobs[P.job];
-      const int j = step(J, a, i, o, 1);
-      double w;
-      if (j >= 0) {
-        if (!w_tail(J, a.n_off, P.field, i, j, o, &w)) {
-          *a.err = 1;
-        } else {
-          const double cand = __dadd_rn(P.tau[i], w);
-          if (cand < P.tau[j]) {
-            const unsigned long long old =
-                atomicMin((unsigned long long*)&P.tau[j], dbits(cand));
-            if (dbits(cand) < old) {
-              out = ((int64_t)p << 32) | (int64_t)j;
-              if (cand < a.thr[p]) want = atomicExch(&P.stamp[j], it + 1) != it + 1;
-              else later = atomicExch(&P.fstamp[j], epoch + 1) != epoch + 1;
+  for (int64_t f = wave; f < n_near; f += n_waves) {
+    const int64_t item = lin[f];
+    const int p = (int)(item >> 32);
+    const int i = (int)(item & 0xffffffffLL);
+    const ProbF P = a.probs[p];
+    const JobF J = a.jobs[P.job];
+    const int x = i % J.nx, r = i / J.nx, y = r % J.ny, z = r / J.ny;
+    const double ti = P.tau[i];
+    const double thr = a.thr[p];
+    const int ci = J.per_node ? 0 : J.cls[i];
+    raw += a.n_off;
+    for (int o0 = 0; o0 < a.n_off; o0 += 64) {
+      const int o = o0 + lane;
+      bool want = false, later = false;
+      int64_t out = 0;
+      if (o < a.n_off) {
+        const int X = x + a.ox[o], Y = y + a.oy[o], Z = z + a.oz[o];
+        if (X >= 0 && X < J.nx && Y >= 0 && Y < J.ny && Z >= 0 && Z < J.nz) {
+          const int j = X + J.nx * (Y + J.ny * Z);
+          double w;
+          if (!w_out(J, a.n_off, P.field, i, ci, j, o, &w)) {
+            *a.err = 1;
+          } else {
+            const double cand = __dadd_rn(ti, w);
+            if (cand < P.tau[j]) {
+              const unsigned long long old =
+                  atomicMin((unsigned long long*)&P.tau[j], dbits(cand));
+              if (dbits(cand) < old) {
+                out = ((int64_t)p << 32) | (int64_t)j;
+                if (cand < thr) want = atomicExch(&P.stamp[j], it + 1) != it + 1;
+                else later = atomicExch(&P.fstamp[j], epoch + 1) != epoch + 1;
+              }
             }
           }
         }
       }
+      append64(want, out, lout, &a.counts[it + 1]);
+      append64(later, out, far, &a.far_count[epoch & 1]);
     }
-    append64(want, out, lout, &a.counts[it + 1]);
-    append64(later, out, a.far + (int64_t)(epoch & 1) * a.cap, &a.far_count[epoch & 1]);
   }
-  for (int off = 32; off > 0; off >>= 1) raw += __shfl_xor(raw, off);
-  if (__lane_id() == 0 && raw) atomicAdd(&a.stats[1], (unsigned long long)raw);
+  if (lane == 0 && raw) atomicAdd(&a.stats[1], (unsigned long long)raw);
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.stats[0], 1ull);
 }
 
@@ -341,33 +349,38 @@ __global__ void __launch_bounds__(kFrontierThreads) k_front_hop(RF a, int k) {
   const int start = a.seg[k], cnt = a.counts[k];
   if (blockIdx.x == 0 && threadIdx.x == 0) a.seg[k + 1] = start + cnt;
   if (cnt == 0) return;
-  const int64_t total = (int64_t)cnt * a.n_off;
   int64_t* out = a.lists + start + cnt;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
-    const int64_t t = base + threadIdx.x;
-    bool want = false;
-    int64_t item_j = 0;
-    if (t < total) {
-      const int64_t f = t / a.n_off;
-      const int o = (int)(t - f * a.n_off);
-      const int64_t item = a.lists[start + f];
-      const int p = (int)(item >> 32);
-      const int i = (int)(item & 0xffffffffLL);
-      const ProbF P = a.probs[p];
-      const JobF J = a.jobs[P.job];
-      const int j = step(J, a, i, o, 1);
-      double w;
-      if (j >= 0) {
-        const double tj = P.tau[j];
-        if (tj < INFINITY && w_tail(J, a.n_off, P.field, i, j, o, &w) &&
-            __dadd_rn(P.tau[i], w) == tj && atomicMin(&P.stamp[j], k + 1) > k + 1) {
-          want = true;
-          item_j = ((int64_t)p << 32) | (int64_t)j;
+  const int lane = __lane_id();
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t f = wave; f < cnt; f += n_waves) {  // one wavefront per item
+    const int64_t item = a.lists[start + f];
+    const int p = (int)(item >> 32);
+    const int i = (int)(item & 0xffffffffLL);
+    const ProbF P = a.probs[p];
+    const JobF J = a.jobs[P.job];
+    const int x = i % J.nx, r = i / J.nx, y = r % J.ny, z = r / J.ny;
+    const double ti = P.tau[i];
+    const int ci = J.per_node ? 0 : J.cls[i];
+    for (int o0 = 0; o0 < a.n_off; o0 += 64) {
+      const int o = o0 + lane;
+      bool want = false;
+      int64_t item_j = 0;
+      if (o < a.n_off) {
+        const int X = x + a.ox[o], Y = y + a.oy[o], Z = z + a.oz[o];
+        if (X >= 0 && X < J.nx && Y >= 0 && Y < J.ny && Z >= 0 && Z < J.nz) {
+          const int j = X + J.nx * (Y + J.ny * Z);
+          const double tj = P.tau[j];
+          double w;
+          if (tj < INFINITY && w_out(J, a.n_off, P.field, i, ci, j, o, &w) &&
+              __dadd_rn(ti, w) == tj && atomicMin(&P.stamp[j], k + 1) > k + 1) {
+            want = true;
+            item_j = ((int64_t)p << 32) | (int64_t)j;
+          }
         }
       }
+      append64(want, item_j, out, &a.counts[k + 1]);
     }
-    append64(want, item_j, out, &a.counts[k + 1]);
   }
 }
 
