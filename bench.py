@@ -39,12 +39,12 @@ FP64_VALU_PEAK_TOPS = 39.3  # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz, one o
 # Valid only for the kernel source it was measured on.
 MEASURED_TRAFFIC = {
     "source": "paper_2609_26108_amd/csrc/trace.hip",
-    "source_sha256_16": "f46395b9bb8c4f2a",
+    "source_sha256_16": "e2268df0f7dc3ee7",
     "fetch_scale": 2.0, "write_scale": 1.0,
     "kib_per_dispatch": {  # kernel -> (FETCH_SIZE KiB, WRITE_SIZE KiB)
-        "k_relax_tau": (2438.8, 731.3),
-        "k_relax_hop": (3053.1, 233.1),
-        "k_relax_tstar": (1576.4, 173.9),
+        "k_relax_tau": (2450.5, 731.5),
+        "k_relax_hop": (3065.8, 233.4),
+        "k_relax_tstar": (1585.9, 173.9),
     },
 }
 
@@ -71,9 +71,9 @@ def measured_traffic_bytes(kernel):
 MEASURED_FP64 = {
     "sources": ["paper_2609_26108_amd/csrc/cache_build.hip",
                 "paper_2609_26108_amd/csrc/physics.h", "paper_2609_26108_amd/csrc/mlp.h"],
-    "sources_sha256_16": "1b6627ce68c0eb0f",
-    "flops_per_dispatch": {"k_warm_solve": 7.4710e11, "k_warm_window": 5.4837e11,
-                           "k_warm_predict": 5.3496e9},
+    "sources_sha256_16": "89e2c5c1888fe73e",
+    "flops_per_dispatch": {"k_warm_solve": 7.4710e11, "k_warm_window": 3.8901e11,
+                           "k_warm_fold": 2.1129e10, "k_warm_predict": 5.3496e9},
 }
 
 
