@@ -222,3 +222,31 @@ def test_trace_3d_autotuned_bucket(G, small3d):
         ref = O.trace_3d(m.nx, m.ny, m.nz, m.h, m.h, m.h, m.class_id, m.radius, f[0, 1], f[1, 1],
                          s[1], src, N=400)
         assert np.array_equal(tr[si].cpu().numpy(), ref["tauR"])
+
+
+def test_trace_3d_raypaths(G, small3d):
+    """Raypaths (eqs 25, 33-34) from the GPU's 3D propagation predecessors:
+    chert_extract_raypath gives the oracle's node sequence for sampled
+    reachable receivers of the first source, each step a star offset."""
+    Cm = C()
+    m, cls, f, s = small3d
+    K = cls.shape[0]
+    desc = Cm.cache_desc(dim=3, n_dirs=400, modes=(0, 1), n_sweep=360)
+    cache = G.import_cache(f, s, desc, K)
+    g, _ = trace3(G, m, cache, desc, K, 1, 16.0, full=True)
+    src = m.sources[0]
+    o = O.trace_3d(m.nx, m.ny, m.nz, m.h, m.h, m.h, m.class_id, m.radius, f[0, 1], f[1, 1], s[1],
+                   src, N=400)
+    ox, oy, oz, _, _ = Cm.chert_star_3d(m.radius, m.h, m.h, m.h, 400)
+    star = set(zip(ox.tolist(), oy.tolist(), oz.tolist()))
+    pred = g["predP"][0]
+    reach = np.flatnonzero(np.isfinite(g["tauR"][0]))
+    rng = np.random.default_rng(9)
+    for rcv in rng.choice(reach, 60, replace=False):
+        p = Cm.chert_extract_raypath(pred, src, int(rcv))
+        rc, q = O.raypath(o["predP"], src, int(rcv))
+        assert rc == 0 and np.array_equal(p, q), rcv
+        assert p[0] == src and p[-1] == rcv
+        xyz = np.stack([p % m.nx, (p // m.nx) % m.ny, p // (m.nx * m.ny)], 1)
+        for d in np.diff(xyz, axis=0):
+            assert tuple(int(v) for v in d) in star
