@@ -771,7 +771,12 @@ def run_3d(args):
     t0 = time.perf_counter()
     probe_ms = C.chert_trace_autotune(b, opts, tws, stream=stream)
     tune = {"s": time.perf_counter() - t0, "probe_ms": probe_ms,
-            "bucket_width": opts.bucket_width}
+            "launch": LAUNCH_NAMES[opts.launch]}
+    if opts.launch == C.LAUNCH_FRONTIER:
+        tune["bucket_width"] = opts.bucket_width
+    else:  # 3D tiles tile_x x tile_x x tile_z
+        tune["tile"] = [opts.tile_x, opts.tile_x, opts.tile_z]
+        tune["push_group"] = opts.push_group
     ox, oy, oz, _, _ = C.chert_star_3d(m.radius, m.h, m.h, m.h, m.n_dirs)
     E = useful_edges_3d(m.nx, m.ny, m.nz, ox, oy, oz)
     times = {"build": [], "trace": []}
@@ -801,7 +806,8 @@ def run_3d(args):
            "trace_s": tt, "useful_edges_per_field": E,
            "useful_edge_relaxations_per_s": E * fields / tt,
            "raw_over_useful": stats.edge_relaxations[0] / (E * fields),
-           "iterations": stats.rounds[0], "repeats": len(times["trace"]), "autotune": tune,
+           "iterations_or_rounds": stats.rounds[0], "repeats": len(times["trace"]),
+           "autotune": tune,
            "ms_per_step": 1e3 * (tb + tt)}
     res["value"] = res["useful_edge_relaxations_per_s"]
     res["unit"] = "useful edge relaxations/s (3D trace, 16 fields)"

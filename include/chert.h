@@ -198,9 +198,9 @@ int chert_build_cache(const chert_cache_desc *d, const chert_class *classes_dev,
  * the bin of o is the Fibonacci direction with the largest dot product with
  * o / L_o (lowest index on ties).  3D traces (with a class map and a 3D
  * cache) give every output of the 2D path by the same rules; the relaxation
- * is a node-frontier label-correcting iteration with near/far buckets
- * (chert_trace_opts.bucket_width) and the same fixed point; predecessors
- * come from BFS layers over tight edges. */
+ * runs on 3D tiles or on a node frontier with near/far buckets (see
+ * chert_trace_opts.launch) to the same fixed point; predecessors come from
+ * BFS layers over tight edges. */
 typedef struct chert_grid {
   int32_t dim;                 /* 2 or 3                                   */
   int32_t radius;              /* forward-star radius R, 1..8 (3D: 1..4)   */
@@ -247,7 +247,12 @@ typedef struct chert_trace_stats {
  *               atomicMin on the head, optional near/far buckets), one launch
  *               per iteration, the host checking the frontier sizes every 8
  *               iterations; predecessors from BFS layers over tight edges.
- *               3D batches always run this way, whatever `launch` says.
+ * 3D batches: CHERT_LAUNCH_FRONTIER runs the node frontier;
+ * CHERT_LAUNCH_PER_ROUND runs the traveltimes on 3D tiles of tile_x x
+ * tile_x x tile_z nodes (default 8 x 8 x 8; at least radius per side, at
+ * most 1024 nodes; the same per-round scheme, 26 neighbour tiles) and the
+ * predecessors and t* with the frontier's BFS layers; _PERSISTENT is
+ * UNSUPPORTED in 3D.
  * In per-node mode (no class map) the relaxation may read an edge's weight
  * from either endpoint's row; both hold the same value because a cache
  * stores direction d + n_dirs/2 as the exact copy of d. */
@@ -331,7 +336,8 @@ int chert_trace_batch(const chert_trace_job *jobs, int32_t n_jobs,
  * fixed point does not depend on them (every candidate gives the same
  * fields); only the time does.  Candidates: in 3D the frontier iteration
  * with bucket widths 0 (one bucket), 4, 16, 32, 64, 128, 256 (units of the
- * smallest edge weight); in 2D the frontier with widths 16 and 64 and the
+ * smallest edge weight) and the 3D tiles 8x8x8, 8x8x16, 16x16x4, 4x4x16
+ * with push groups 1, 2, 4; in 2D the frontier with widths 16 and 64 and the
  * tiles 32x32, 64x16, 16x64, 32x16, 16x32, 128x8, 16x16 with push groups 1, 2, 4,
  * per-round and persistent launch, then, if tiles win, their ordering width
  * 16, 64 or 256 on the fastest shape.  Each is timed (HIP events,

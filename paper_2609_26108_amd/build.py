@@ -3,7 +3,7 @@
 Per-file floating-point contraction:
   - cache_build.hip: FMA contraction allowed (the local solve is compared
     with a tolerance);
-  - trace.hip, frontier.hip, abi_host.cpp: -ffp-contract=off, so edge weights, traveltime
+  - trace.hip, frontier.hip, tile3d.hip, abi_host.cpp: -ffp-contract=off, so edge weights, traveltime
     sums and the host-side star lengths are plain IEEE operations.
 """
 from __future__ import annotations
@@ -26,6 +26,7 @@ SOURCES = [
     ("cache_build.hip", ["-ffp-contract=fast"]),
     ("trace.hip", ["-ffp-contract=off"]),
     ("frontier.hip", ["-ffp-contract=off"]),
+    ("tile3d.hip", ["-ffp-contract=off"]),
     ("surrogate.hip", ["-ffp-contract=fast"]),
     ("abi_host.cpp", ["-ffp-contract=off", "-x", "hip"]),
 ]

@@ -58,6 +58,28 @@ size_t trace_batch_frontier_bytes(const chert_trace_job* jobs, int n_jobs,
 int enqueue_wmin_init(double* wmin, hipStream_t s);
 int enqueue_wmin(const double* W, int64_t per_field, double* wmin, hipStream_t s);
 
+// 3D tiles for the traveltime phase of a 3D batch (tile3d.hip): one job per
+// grid (class map, class-pair table [2][K][K][n_off] on the device), one
+// problem per (source, field).  The star offsets are device arrays.  Runs the
+// rounds to convergence on s (host checks every 8 rounds); tau must hold its
+// initial values (0 at the source, +inf elsewhere).
+struct Tile3Job {
+  int nx, ny, nz, K;
+  const int32_t* cls;
+  const double* W;
+};
+struct Tile3Prob {
+  double* tau;
+  int64_t src;
+  int job, field;
+};
+int tiles3d_bytes(const Tile3Job* jobs, int n_jobs, const Tile3Prob* probs, int n_prob, int R,
+                  int n_off, int tile_x, int tile_z, int max_rounds, size_t* bytes);
+int relax_tiles_3d(const Tile3Job* jobs, int n_jobs, const Tile3Prob* probs, int n_prob,
+                   const int32_t* ox_dev, const int32_t* oy_dev, const int32_t* oz_dev, int n_off,
+                   int R, int tile_x, int tile_z, int push_group, int max_rounds, void* ws,
+                   size_t ws_bytes, hipStream_t s, int* rounds, int64_t* visits, int64_t* edges);
+
 // 2D job checks shared by the tile and frontier paths (trace.hip).
 int validate_job_2d(const chert_trace_job& j, uint32_t outs);
 // Per-node weight table of a 2D job: W[f][j][o] = the edge j - o -> j

@@ -449,8 +449,9 @@ int enqueue_wmin(const double* W, int64_t per_field, double* wmin, hipStream_t s
 struct PlanF {
   int dim = 0, R = 0, n_off = 0, n_prob = 0, max_iter = 0;
   int64_t cap = 0;
+  bool tiles = false;  // 3D traveltimes on tiles (tile3d.hip) instead of the frontier
   size_t off_star = 0, off_lcol = 0, off_jobs = 0, off_probs = 0, off_counts = 0, off_err = 0,
-         off_lists = 0, off_far = 0, off_thr = 0, off_lut = 0, total = 0;
+         off_lists = 0, off_far = 0, off_thr = 0, off_lut = 0, off_tiles = 0, total = 0;
   std::vector<size_t> off_W, off_stamp;  // per job, per problem (near and far stamps)
 };
 
@@ -567,6 +568,26 @@ static int make_plan_f(const chert_trace_job* jobs, int n_jobs, const chert_trac
   off += (o->bucket_width > 0.0) ? align256((size_t)2 * P->cap * sizeof(int64_t)) : 0;
   P->off_thr = off;
   off += align256((size_t)2 * P->n_prob * sizeof(double) + 4 * sizeof(double));
+  if (P->dim == 3 && o->launch == CHERT_LAUNCH_PERSISTENT)
+    return fail(CHERT_ERR_UNSUPPORTED, "3D batches run per-round tiles or the node frontier");
+  P->tiles = P->dim == 3 && o->launch == CHERT_LAUNCH_PER_ROUND;
+  if (P->tiles) {
+    if (o->push_group != 0 && o->push_group != 1 && o->push_group != 2 && o->push_group != 4)
+      return fail(CHERT_ERR_INVALID_ARG, "push_group must be 0, 1, 2 or 4");
+    std::vector<Tile3Job> tj(n_jobs);
+    std::vector<Tile3Prob> tp;
+    for (int j = 0; j < n_jobs; ++j) {
+      const chert_grid* g = jobs[j].g;
+      tj[j] = Tile3Job{(int)g->nx, (int)g->ny, (int)g->nz, (int)jobs[j].n_classes, nullptr, nullptr};
+      for (int q = 0; q < per * jobs[j].n_src; ++q) tp.push_back(Tile3Prob{nullptr, 0, j, 0});
+    }
+    size_t tb = 0;
+    const int rc = tiles3d_bytes(tj.data(), n_jobs, tp.data(), (int)tp.size(), P->R, P->n_off,
+                                 o->tile_x, o->tile_z, P->max_iter, &tb);
+    if (rc) return rc;
+    P->off_tiles = off;
+    off += align256(tb);
+  }
   P->total = off;
   return CHERT_OK;
 }
@@ -728,6 +749,21 @@ int trace_batch_frontier(const chert_trace_job* jobs, int n_jobs, const chert_tr
   const int group = 8;
   int iters = -1, epoch = 0;
   int32_t counts[group + 2];
+  int64_t tile_visits = 0, tile_edges = 0;
+  if (P.tiles) {  // 3D: the traveltimes on tiles, from the initial fields above
+    std::vector<Tile3Job> tj(n_jobs);
+    for (int j = 0; j < n_jobs; ++j)
+      tj[j] = Tile3Job{jd[j].nx, jd[j].ny, jd[j].nz, jd[j].K, jd[j].cls, jd[j].W};
+    std::vector<Tile3Prob> tp(pd.size());
+    for (size_t q = 0; q < pd.size(); ++q)
+      tp[q] = Tile3Prob{pd[q].tau, pd[q].src, pd[q].job, pd[q].field};
+    int rounds = 0;
+    rc = relax_tiles_3d(tj.data(), n_jobs, tp.data(), (int)tp.size(), a.ox, a.oy, a.oz, P.n_off,
+                        P.R, o->tile_x, o->tile_z, o->push_group, P.max_iter, ws + P.off_tiles,
+                        P.total - P.off_tiles, s, &rounds, &tile_visits, &tile_edges);
+    if (rc) return rc;
+    iters = rounds;
+  }
   for (int it = 0; it < P.max_iter && iters < 0;) {
     const int nb = it + group > P.max_iter ? P.max_iter - it : group;
     for (int q = 0; q < nb; ++q)
@@ -796,8 +832,8 @@ int trace_batch_frontier(const chert_trace_job* jobs, int n_jobs, const chert_tr
     *st = chert_trace_stats{};
     st->rounds[0] = iters < 0 ? P.max_iter : iters;
     st->rounds[1] = layers;
-    st->tile_visits[0] = (int64_t)hstats[0];
-    st->edge_relaxations[0] = (int64_t)hstats[1];
+    st->tile_visits[0] = P.tiles ? tile_visits : (int64_t)hstats[0];
+    st->edge_relaxations[0] = P.tiles ? tile_edges : (int64_t)hstats[1];
   }
   if (iters < 0) return fail(CHERT_ERR_NO_CONVERGENCE, "relaxation iteration cap reached");
   if (herr) return fail(CHERT_ERR_INVALID_ARG, "class id out of range");

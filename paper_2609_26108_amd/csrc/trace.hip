@@ -1777,6 +1777,7 @@ extern "C" int chert_trace_field(const chert_cache_desc* d, const void* cache_de
 
 namespace {
 const int kTuneTiles[][2] = {{32, 32}, {64, 16}, {16, 64}, {32, 16}, {16, 32}, {128, 8}, {16, 16}};
+const int kTuneTiles3D[][2] = {{8, 8}, {8, 16}, {16, 4}, {4, 16}};
 const int kTuneGroups[] = {1, 2, 4};
 const int kTuneLaunch[] = {CHERT_LAUNCH_PER_ROUND, CHERT_LAUNCH_PERSISTENT};
 }  // namespace
@@ -1795,7 +1796,18 @@ extern "C" size_t chert_trace_autotune_workspace_bytes(const chert_trace_job* jo
   f.launch = CHERT_LAUNCH_FRONTIER;
   f.bucket_width = 1.0;
   size_t best = chert_trace_batch_workspace_bytes(jobs, n_jobs, &f);
-  if (is_3d_batch(jobs, n_jobs)) return best;
+  if (is_3d_batch(jobs, n_jobs)) {
+    for (const auto& t : kTuneTiles3D) {
+      chert_trace_opts c = *o;
+      c.tile_x = t[0];
+      c.tile_z = t[1];
+      c.launch = CHERT_LAUNCH_PER_ROUND;
+      c.bucket_width = 1.0;
+      const size_t b = chert_trace_batch_workspace_bytes(jobs, n_jobs, &c);
+      if (b > best) best = b;
+    }
+    return best;
+  }
   for (const auto& t : kTuneTiles) {
     chert_trace_opts c = *o;
     c.tile_x = t[0];
@@ -1827,6 +1839,17 @@ extern "C" int chert_trace_autotune(const chert_trace_job* jobs, int32_t n_jobs,
     c.bucket_width = bws[q];
     cands.push_back(c);
   }
+  if (three_d)  // 3D tiles (tile_x x tile_x x tile_z), per-round launches
+    for (const auto& t : kTuneTiles3D)
+      for (int G : kTuneGroups) {
+        chert_trace_opts c = *o;
+        c.tile_x = t[0];
+        c.tile_z = t[1];
+        c.push_group = G;
+        c.launch = CHERT_LAUNCH_PER_ROUND;
+        c.bucket_width = 0.0;
+        cands.push_back(c);
+      }
   if (!three_d)
     for (const auto& t : kTuneTiles)
       for (int G : kTuneGroups)

@@ -97,15 +97,17 @@ def small3d():
     return m, cls, f, s
 
 
-def trace3(G, m, cache, desc, K, mode, bucket=0.0, full=False):
+def trace3(G, m, cache, desc, K, mode, bucket=0.0, full=False, launch=2, tile=(0, 0), group=0):
     """tau_R, tau_I (and with full=True also t*, pred_P, pred_A) of every
-    source; returns numpy arrays and the counters."""
+    source; launch 2 = node frontier, 0 = 3D tiles (tile_x, tile_z); returns
+    numpy arrays and the counters."""
     Cm = C()
     cid = torch.from_numpy(np.ascontiguousarray(m.class_id.reshape(-1), dtype=np.int32)).to(G.DEV)
     g = Cm.make_grid3(m.nx, m.ny, m.nz, m.h, m.radius, cid)
     stats = Cm.TraceStats()
     outs = Cm.OUT_ALL if full else Cm.OUT_TAU_R | Cm.OUT_TAU_I
-    o = Cm.trace_opts(outs, stats=stats, bucket_width=bucket)
+    o = Cm.trace_opts(outs, tile[0], tile[1], stats=stats, bucket_width=bucket, launch=launch,
+                      push_group=group)
     S, n = len(m.sources), m.n_nodes
     tr = torch.empty((S, n), dtype=torch.float64, device=G.DEV)
     ti = torch.empty((S, n), dtype=torch.float64, device=G.DEV)
@@ -122,18 +124,22 @@ def trace3(G, m, cache, desc, K, mode, bucket=0.0, full=False):
     return tr.cpu().numpy(), ti.cpu().numpy(), stats.as_dict()
 
 
-@pytest.mark.parametrize("bucket", [0.0, 3.0, 16.0])
-def test_trace_3d_imported_cache_bitwise(G, small3d, bucket):
+@pytest.mark.parametrize("launch,bucket,tile,group", [
+    (2, 0.0, (0, 0), 0), (2, 3.0, (0, 0), 0), (2, 16.0, (0, 0), 0),
+    (0, 0.0, (0, 0), 0), (0, 0.0, (4, 16), 1), (0, 0.0, (16, 4), 4), (0, 0.0, (3, 3), 2)])
+def test_trace_3d_imported_cache_bitwise(G, small3d, launch, bucket, tile, group):
     """On the oracle's cache, every 3D traveltime (three sources, two modes,
-    tau_R and tau_I) equals the oracle's Dijkstra bitwise, with one frontier
-    bucket or near/far buckets of several widths."""
+    tau_R and tau_I) equals the oracle's Dijkstra bitwise: on the node
+    frontier with one bucket or near/far buckets of several widths, and on
+    3D tiles of several shapes (ragged at the grid's far faces)."""
     Cm = C()
     m, cls, f, s = small3d
     K = cls.shape[0]
     desc = Cm.cache_desc(dim=3, n_dirs=400, modes=(0, 1), n_sweep=360)
     cache = G.import_cache(f, s, desc, K)
     for mode in (0, 1):
-        tr, ti, st = trace3(G, m, cache, desc, K, mode, bucket)
+        tr, ti, st = trace3(G, m, cache, desc, K, mode, bucket, launch=launch, tile=tile,
+                            group=group)
         print("mode", mode, st)
         for si, src in enumerate(m.sources):
             o = O.trace_3d(m.nx, m.ny, m.nz, m.h, m.h, m.h, m.class_id, m.radius, f[0, mode],
@@ -142,8 +148,8 @@ def test_trace_3d_imported_cache_bitwise(G, small3d, bucket):
             assert np.array_equal(ti[si], o["tauI"]), (mode, si)
 
 
-@pytest.mark.parametrize("bucket", [0.0, 16.0])
-def test_trace_3d_predecessors_and_tstar_bitwise(G, small3d, bucket):
+@pytest.mark.parametrize("launch,bucket", [(2, 0.0), (2, 16.0), (0, 0.0)])
+def test_trace_3d_predecessors_and_tstar_bitwise(G, small3d, launch, bucket):
     """Predecessors of both fields (BFS hop over tight edges, then the
     smallest offset index) and t* along the propagation tree equal the
     oracle's, bitwise, for every source and both modes."""
@@ -153,7 +159,7 @@ def test_trace_3d_predecessors_and_tstar_bitwise(G, small3d, bucket):
     desc = Cm.cache_desc(dim=3, n_dirs=400, modes=(0, 1), n_sweep=360)
     cache = G.import_cache(f, s, desc, K)
     for mode in (0, 1):
-        g, st = trace3(G, m, cache, desc, K, mode, bucket, full=True)
+        g, st = trace3(G, m, cache, desc, K, mode, bucket, full=True, launch=launch)
         print("mode", mode, st)
         for si, src in enumerate(m.sources):
             o = O.trace_3d(m.nx, m.ny, m.nz, m.h, m.h, m.h, m.class_id, m.radius, f[0, mode],
@@ -163,16 +169,17 @@ def test_trace_3d_predecessors_and_tstar_bitwise(G, small3d, bucket):
                                                             int(np.sum(g[key][si] != o[key])))
 
 
-def test_trace_3d_end_to_end(G, small3d):
-    """GPU cache -> GPU 3D trace against oracle cache -> oracle Dijkstra:
-    1e-9 relative."""
+@pytest.mark.parametrize("launch", [0, 2])
+def test_trace_3d_end_to_end(G, small3d, launch):
+    """GPU cache -> GPU 3D trace (tiles or frontier) against oracle cache ->
+    oracle Dijkstra: 1e-9 relative."""
     Cm = C()
     m, cls, f, s = small3d
     K = cls.shape[0]
     desc = Cm.cache_desc(dim=3, n_dirs=400, modes=(0, 1), n_sweep=360)
     cache = G.build_cache(G.classes_from_arrays(cls), desc)
     for mode in (0, 1):
-        tr, ti, _ = trace3(G, m, cache, desc, K, mode)
+        tr, ti, _ = trace3(G, m, cache, desc, K, mode, launch=launch)
         o = O.trace_3d(m.nx, m.ny, m.nz, m.h, m.h, m.h, m.class_id, m.radius, f[0, mode],
                        f[1, mode], s[mode], m.sources[0], N=400)
         for a, b in ((tr[0], o["tauR"]), (ti[0], o["tauI"])):
@@ -182,7 +189,8 @@ def test_trace_3d_end_to_end(G, small3d):
             assert rel.max() <= 1e-9, rel.max()
 
 
-def test_trace_3d_invalid_class_id_reported(G, small3d):
+@pytest.mark.parametrize("launch", [0, 2])
+def test_trace_3d_invalid_class_id_reported(G, small3d, launch):
     Cm = C()
     m, cls, f, s = small3d
     K = cls.shape[0]
@@ -192,7 +200,7 @@ def test_trace_3d_invalid_class_id_reported(G, small3d):
     bad[7, 5, 5] = K + 3
     m2 = W.Model3D(m.name, m.nx, m.ny, m.nz, m.h, m.layers, bad, m.sources, m.modes, m.radius)
     with pytest.raises(Cm.ChertError) as e:
-        trace3(G, m2, cache, desc, K, 0)
+        trace3(G, m2, cache, desc, K, 0, launch=launch)
     assert e.value.code == 1
 
 
@@ -213,8 +221,12 @@ def test_trace_3d_autotuned_bucket(G, small3d):
     ws = torch.empty(Cm.chert_trace_autotune_workspace_bytes(b, o), dtype=torch.uint8,
                      device=G.DEV)
     ms = Cm.chert_trace_autotune(b, o, ws)
-    print("3D autotuned bucket", o.bucket_width, ms)
-    assert o.bucket_width in (0.0, 4.0, 16.0, 32.0, 64.0, 128.0, 256.0)
+    print("3D autotuned", o.launch, o.bucket_width, o.tile_x, o.tile_z, o.push_group, ms)
+    if o.launch == Cm.LAUNCH_FRONTIER:
+        assert o.bucket_width in (0.0, 4.0, 16.0, 32.0, 64.0, 128.0, 256.0)
+    else:
+        assert o.launch == Cm.LAUNCH_PER_ROUND and (o.tile_x, o.tile_z) in (
+            (8, 8), (8, 16), (16, 4), (4, 16))
     tr.fill_(-1.0)
     Cm.chert_trace_batch(b, o, ws)
     torch.cuda.synchronize()
@@ -233,7 +245,7 @@ def test_trace_3d_raypaths(G, small3d):
     K = cls.shape[0]
     desc = Cm.cache_desc(dim=3, n_dirs=400, modes=(0, 1), n_sweep=360)
     cache = G.import_cache(f, s, desc, K)
-    g, _ = trace3(G, m, cache, desc, K, 1, 16.0, full=True)
+    g, _ = trace3(G, m, cache, desc, K, 1, 16.0, full=True, launch=2)
     src = m.sources[0]
     o = O.trace_3d(m.nx, m.ny, m.nz, m.h, m.h, m.h, m.class_id, m.radius, f[0, 1], f[1, 1], s[1],
                    src, N=400)
