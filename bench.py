@@ -39,12 +39,12 @@ FP64_VALU_PEAK_TOPS = 39.3  # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz, one o
 # Valid only for the kernel source it was measured on.
 MEASURED_TRAFFIC = {
     "source": "paper_2609_26108_amd/csrc/trace.hip",
-    "source_sha256_16": "e2268df0f7dc3ee7",
+    "source_sha256_16": "506caa21f66c0bc5",
     "fetch_scale": 2.0, "write_scale": 1.0,
     "kib_per_dispatch": {  # kernel -> (FETCH_SIZE KiB, WRITE_SIZE KiB)
         "k_relax_tau": (2450.5, 731.5),
         "k_relax_hop": (3065.8, 233.4),
-        "k_relax_tstar": (1585.9, 173.9),
+        "k_relax_tstar": (1586.0, 173.9),
     },
 }
 
