@@ -43,8 +43,6 @@ MEASURED_TRAFFIC = {
     "fetch_scale": 2.0, "write_scale": 1.0,
     "kib_per_dispatch": {  # kernel -> (FETCH_SIZE KiB, WRITE_SIZE KiB)
         "k_relax_tau": (2450.5, 731.5),
-        "k_relax_hop": (3065.8, 233.4),
-        "k_relax_tstar": (1586.0, 173.9),
     },
 }
 
@@ -273,13 +271,8 @@ def main():
     # tau tiles, class ids and the class-pair weight table on chip, so its
     # algorithmic work is FP64 VALU: one add and one compare per useful edge
     # relaxation; peak = 78.6 TFLOP/s (FMA counted twice) / 2 = 39.3 T ops/s.
-    phases = {"k_relax_tau": 0, "k_relax_hop": 1, "k_relax_tstar": 2,
-              "k_relax_persist_tau": 0, "k_relax_persist_hop": 1, "k_relax_persist_tstar": 2,
-              "k_front_relax": 0, "k_front_hop": 1, "k_front_tstar": 2}
-    if dom in phases:
-        phase = phases[dom]
-        useful_phase = {0: edges_per_step, 1: edges_per_step, 2: E * len(m.modes)}[phase]
-        per_launch_ops = 2.0 * useful_phase / kernels[dom]["launches_per_step"]
+    if dom in ("k_relax_tau", "k_relax_persist_tau", "k_front_relax"):
+        per_launch_ops = 2.0 * edges_per_step / kernels[dom]["launches_per_step"]
         achieved = per_launch_ops / (kernels[dom]["avg_us"] * 1e-6) / 1e12
         traffic = measured_traffic_bytes(dom)
         roof = {"kernel": dom, "bound": "alu", "achieved": achieved,

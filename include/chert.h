@@ -218,10 +218,13 @@ enum {
   CHERT_OUT_PRED_A = 16
 };
 
-/* Work counters of one trace call, per phase (0 = traveltimes, 1 = hop
- * counts for the predecessors, 2 = t*).  Frontier runs fill rounds[0] =
- * iterations, rounds[1] = BFS layers, tile_visits[0] = iterations that had
- * work and edge_relaxations[0] = (frontier node, offset) pairs examined. */
+/* Work counters of one trace call, per phase.  Tile runs (2D): 0 =
+ * traveltimes, 1 = the predecessor tree (hop counts, predecessors and t*
+ * in one relaxation over the tight edges), slot 2 unused (0).  3D tile
+ * runs fill slot 0 and rounds[1] = BFS layers.  Frontier runs fill
+ * rounds[0] = iterations, rounds[1] = BFS layers, tile_visits[0] =
+ * iterations that had work and edge_relaxations[0] = (frontier node,
+ * offset) pairs examined. */
 typedef struct chert_trace_stats {
   int32_t rounds[3];           /* relaxation rounds until no tile changed   */
   int32_t reserved;

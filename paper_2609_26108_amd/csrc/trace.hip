@@ -17,10 +17,12 @@
 // values only decrease, so the fixed point is the minimum over paths --
 // bitwise what Dijkstra computes from the same weights, for any schedule.
 //
-// Predecessors (eq 33) are schedule-independent: BFS hop counts over the
-// tight edges (tau_i + w_ij == tau_j) by the same tiled relaxation, then
-// pred_j = tight neighbour with the smallest (hop, offset index).  t* folds
-// the attenuation increments along the propagation predecessor tree.
+// Predecessors (eq 33) are schedule-independent: once tau is final, the
+// tight edges (tau_i + w_ij == tau_j) are fixed; a second tiled relaxation
+// over them takes, per node, the smallest (hop_i + 1, offset index) over
+// its tight in-edges (BFS layers with eq 33's tie rule) and, on the
+// propagation problems, folds t* (the attenuation increments) along the
+// predecessor tree in the same pass.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -40,7 +42,7 @@ constexpr int kRelaxThreads = 1024;  // one node per thread: tiles <= 1024 nodes
 // threads of a tile workgroup: the tile's nodes rounded up to whole wavefronts
 static inline int tile_threads(int tx, int tz) { return (tx * tz + 63) / 64 * 64; }
 constexpr int kLocalIterCap = 4096;
-constexpr int32_t kHopUnset = 0x7fffffff;
+constexpr unsigned long long kKeyUnset = ~0ull;  // tree phase: node not reached
 constexpr int kFieldR = 0, kFieldI = 1;
 constexpr size_t kWLdsBytes = 48 * 1024;  // class-pair table staged in LDS up to this
 // Tile flag bits.  Between two visits of a tile only its halo can change
@@ -87,8 +89,9 @@ __device__ __forceinline__ double w_push(const JobDev& jb, const double* Wp, int
 
 struct ProbDev {
   double* tau;     // [n_nodes] this problem's field
-  int32_t* hop;    // [n_nodes] hop counts, then predecessor offset index
-  int32_t* pred;   // [n_nodes] or nullptr
+  unsigned long long* key;  // [n_nodes] hop << 32 | predecessor offset index
+  uint32_t* tight;  // [nw][n_nodes] tight out-edge masks
+  int32_t* pred;   // [n_nodes] or nullptr (no tree phase for the problem)
   double* tstar;   // [n_nodes] or nullptr (propagation problems only)
   int64_t src;
   int job;
@@ -99,6 +102,7 @@ struct ProbDev {
 
 struct RelaxArgs {
   int tx, tz, R, n_off, lw, lh;
+  int nw;               // 32-bit words of a tight-edge mask (n_off bits)
   int n_prob, n_tiles;  // problems, tiles over all problems
   const JobDev* jobs;
   const ProbDev* probs;
@@ -108,12 +112,12 @@ struct RelaxArgs {
   int32_t* list;     // [2][n_tiles] tiles active in a round (by round parity)
   int32_t* counter;  // [max_rounds + 2] tiles active in each round
   int32_t* err;      // out-of-range class ids seen
-  unsigned long long* stats;  // [3 phases][2]: tile visits, raw edges examined
+  unsigned long long* stats;  // [3 slots][2]: tile visits, raw edges (slot 2 unused)
   int w_lds_doubles; // LDS room for W
   // Tile ordering (bucket > 0): a tile activated with key k (the smallest
-  // value among the changed border nodes that woke it: tau, hop count or t*
-  // by phase) is visited in a round only if k <= its problem's smallest
-  // pending key + bucket * wmin (hop phase: + bucket hops); otherwise it
+  // value among the changed border nodes that woke it: tau, or the hop
+  // count in the tree phase) is visited in a round only if k <= its problem's smallest
+  // pending key + bucket * wmin (tree phase: + bucket hops); otherwise it
   // waits, still active, for a later round.
   unsigned long long* key;   // [2][n_tiles] keys (double bits) by round parity
   unsigned long long* pmin;  // [3][n_prob] smallest key per problem, by round mod 3
@@ -226,7 +230,7 @@ __global__ void k_init_fields(const ProbDev* probs, const JobDev* jobs, int32_t*
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * blockDim.x) {
     pr.tau[j] = (j == pr.src) ? 0.0 : INFINITY;
-    pr.hop[j] = (j == pr.src) ? 0 : kHopUnset;
+    if (pr.key) pr.key[j] = (j == pr.src) ? 0ull : kKeyUnset;
     if (pr.tstar) pr.tstar[j] = (j == pr.src) ? 0.0 : NAN;
   }
 }
@@ -242,14 +246,15 @@ __global__ void k_clear_flags(int32_t* flags, int64_t n_flags, int32_t* counter,
   if (tid < 3) bar[tid] = 0u;  // barrier arrivals, generation, abort
 }
 
-// activate the source tile of every problem (t* phase: only problems with t*)
+// activate the source tile of every problem (tree phase: only problems
+// with predecessors)
 __global__ void k_seed_flags(int32_t* flags, int32_t* list, int32_t* counter,
                              const ProbDev* probs, const JobDev* jobs, int n_prob, int tx, int tz,
-                             int tstar_phase, unsigned long long* key, unsigned long long* pmin) {
+                             int tree_phase, unsigned long long* key, unsigned long long* pmin) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_prob) return;
   const ProbDev pr = probs[p];
-  if (tstar_phase && pr.tstar == nullptr) return;
+  if (tree_phase && pr.pred == nullptr) return;
   const JobDev jb = jobs[pr.job];
   int sx = (int)(pr.src % jb.nx), sz = (int)(pr.src / jb.nx);
   const int T = pr.tile_base + (sz / tz) * jb.ntx + (sx / tx);
@@ -272,7 +277,7 @@ struct TileCtx {
 // binary search over the tile bases, read and clear the tile's flag.
 __device__ __forceinline__ double key_delta(const RelaxArgs& a, int phase, int field) {
   if (phase == 1) return a.bucket;  // hop counts
-  const double w = a.wmin[phase == 2 ? kFieldI : field];
+  const double w = a.wmin[field];
   return w < INFINITY ? a.bucket * w : INFINITY;
 }
 
@@ -381,7 +386,6 @@ __device__ __forceinline__ void reset_pmin(const RelaxArgs& a, int round) {
 
 struct Smem {
   double* val;    // [lw*lh] field values
-  int32_t* ival;  // [lw*lh] hop counts / predecessor offsets
   int32_t* cls;   // [lw*lh] class ids (| kHaloBit in the halo); -1 outside, -2 bad id
   int32_t* off;   // [n_off] LDS offsets of the star
   double* W;      // staged class-pair table
@@ -398,8 +402,6 @@ __device__ __forceinline__ Smem carve(const RelaxArgs& a, void* base) {
   p += sizeof(double) * n;
   s.W = (double*)p;
   p += sizeof(double) * a.w_lds_doubles;
-  s.ival = (int32_t*)p;
-  p += sizeof(int32_t) * n;
   s.cls = (int32_t*)p;
   p += sizeof(int32_t) * n;
   s.inq = (int32_t*)p;
@@ -414,13 +416,13 @@ __device__ __forceinline__ Smem carve(const RelaxArgs& a, void* base) {
 
 static size_t lds_bytes(int lw, int lh, int w_doubles, int n_off, int tx, int tz) {
   const size_t n = (size_t)lw * lh;
-  return sizeof(double) * (n + w_doubles) + sizeof(int32_t) * 3 * n +
+  return sizeof(double) * (n + w_doubles) + sizeof(int32_t) * 2 * n +
          sizeof(int32_t) * ((n_off + 1) & ~1) + sizeof(int32_t) * 2 * tx * tz;
 }
 
 // Stage class ids and star offsets of tile + halo.
 __device__ __forceinline__ void load_common(const RelaxArgs& a, const TileCtx& c, const JobDev& jb,
-                                            const Smem& s) {
+                                            int32_t* cls, int32_t* inq, int32_t* off) {
   const int R = a.R, lw = a.lw, n = lw * a.lh;
   for (int q = threadIdx.x; q < n; q += blockDim.x) {
     int gx = c.x0 + (q % lw) - R, gz = c.z0 + (q / lw) - R;
@@ -435,10 +437,10 @@ __device__ __forceinline__ void load_common(const RelaxArgs& a, const TileCtx& c
         if (lx < 0 || lx >= c.txe || lz < 0 || lz >= c.tze) k |= kHaloBit;
       }
     }
-    s.cls[q] = k;
-    s.inq[q] = 0;
+    cls[q] = k;
+    inq[q] = 0;
   }
-  for (int o = threadIdx.x; o < a.n_off; o += blockDim.x) s.off[o] = a.ox[o] + a.oz[o] * lw;
+  for (int o = threadIdx.x; o < a.n_off; o += blockDim.x) off[o] = a.ox[o] + a.oz[o] * lw;
 }
 
 __device__ __forceinline__ const double* stage_w(const RelaxArgs& a, const JobDev& jb, int field,
@@ -527,7 +529,7 @@ __device__ __forceinline__ void relax_tau(const RelaxArgs& a, int round, int T) 
     s_cnt[1] = 0;
     s_cnt[2] = 0;
   }
-  load_common(a, c, jb, s);
+  load_common(a, c, jb, s.cls, s.inq, s.off);
   for (int q = threadIdx.x; q < n; q += blockDim.x) {
     int gx = c.x0 + (q % lw) - R, gz = c.z0 + (q / lw) - R;
     bool in = gx >= 0 && gx < jb.nx && gz >= 0 && gz < jb.nz;
@@ -666,19 +668,115 @@ __device__ __forceinline__ void relax_tau(const RelaxArgs& a, int round, int T) 
   if (threadIdx.x == 0 && s_mask) activate(a, round, c, pr, jb, s_mask, s_key);
 }
 
-// Phase HOP: BFS hop counts over tight edges, h_j <- min(h_j, h_i + 1).
-template <int G>
-__device__ __forceinline__ void relax_hop(const RelaxArgs& a, int round, int T) {
+// ------------------------------------------- predecessor tree phase ---
+// Tight out-edges, once tau is final: bit (o & 31) of word o / 32 at node i
+// is set when j = i + o lies in the grid, both classes are valid, tau_j is
+// finite and tau_i + w_ij == tau_j (eq 33's candidate set).  The set never
+// changes afterwards, so the tree phase reads neither tau nor w_R again.
+// Layout [problem][word][node].  blockIdx.y = problem.
+__global__ void k_tight_out(RelaxArgs a) {
+  const ProbDev pr = a.probs[blockIdx.y];
+  if (!pr.pred) return;
+  const JobDev jb = a.jobs[pr.job];
+  const int n_off = a.n_off, nw = a.nw;
+  const int64_t n = (int64_t)jb.nx * jb.nz;
+  const double* Wf = jb.per_node ? jb.W : jb.W + (int64_t)pr.field * jb.K * jb.K * n_off;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int ix = (int)(i % jb.nx), iz = (int)(i / jb.nx);
+    const int32_t ki = jb.per_node ? 0 : jb.class_id[i];
+    const double ti = pr.tau[i];
+    const bool ok = ki >= 0 && ki < jb.K && ti < INFINITY;
+    for (int w = 0; w < nw; ++w) {
+      uint32_t m = 0u;
+      for (int b = 0; ok && b < 32; ++b) {
+        const int o = w * 32 + b;
+        if (o >= n_off) break;
+        const int jx = ix + a.ox[o], jz = iz + a.oz[o];
+        if (jx < 0 || jx >= jb.nx || jz < 0 || jz >= jb.nz) continue;
+        const int64_t j = (int64_t)jx + (int64_t)jb.nx * jz;
+        const int32_t kj = jb.per_node ? 0 : jb.class_id[j];
+        if (kj < 0 || kj >= jb.K) continue;
+        const double tj = pr.tau[j];
+        if (tj < INFINITY &&
+            __dadd_rn(ti, w_push(jb, Wf, pr.field, ki, kj, o, n_off, i)) == tj)
+          m |= 1u << b;
+      }
+      pr.tight[(int64_t)w * n + i] = m;
+    }
+  }
+}
+
+// key of j when reached from i over offset o: (hop_i + 1, o), compared as
+// one 64-bit word, so min over the tight in-edges is eq 33's choice
+__device__ __forceinline__ unsigned long long tree_key(unsigned long long ki, int o) {
+  return (((ki >> 32) + 1ull) << 32) | (unsigned long long)(unsigned)o;
+}
+
+struct TreeSmem {
+  unsigned long long* key;  // [lw*lh] hop << 32 | predecessor offset index
+  double* ts;               // [lw*lh] t* (NaN while unknown)
+  uint32_t* om;             // [nw][lw*lh] tight out-masks
+  int32_t* cls;
+  int32_t* inq;             // (level + 1) << 1 | key changed at that level
+  int32_t* off;
+  int32_t* l0;              // frontiers (interior LDS indices)
+  int32_t* l1;
+  int32_t* lc;              // candidates of a level before the t* check
+};
+
+__device__ __forceinline__ TreeSmem carve_tree(const RelaxArgs& a, void* base) {
+  TreeSmem s;
+  const int n = a.lw * a.lh, T = a.tx * a.tz;
+  char* p = (char*)base;
+  s.key = (unsigned long long*)p;
+  p += sizeof(unsigned long long) * n;
+  s.ts = (double*)p;
+  p += sizeof(double) * n;
+  s.om = (uint32_t*)p;
+  p += sizeof(uint32_t) * a.nw * n;
+  s.cls = (int32_t*)p;
+  p += sizeof(int32_t) * n;
+  s.inq = (int32_t*)p;
+  p += sizeof(int32_t) * n;
+  s.off = (int32_t*)p;
+  p += sizeof(int32_t) * ((a.n_off + 1) & ~1);
+  s.l0 = (int32_t*)p;
+  p += sizeof(int32_t) * T;
+  s.l1 = (int32_t*)p;
+  p += sizeof(int32_t) * T;
+  s.lc = (int32_t*)p;
+  return s;
+}
+
+static size_t tree_lds_bytes(int lw, int lh, int nw, int n_off, int tx, int tz) {
+  const size_t n = (size_t)lw * lh;
+  return (2 * sizeof(double) + sizeof(uint32_t) * nw + 2 * sizeof(int32_t)) * n +
+         sizeof(int32_t) * ((n_off + 1) & ~1) + sizeof(int32_t) * 3 * tx * tz;
+}
+
+// Phase TREE: hop counts, predecessors (eq 33) and t* in one relaxation.
+// key_j = min over tight in-edges i -> j of (hop_i + 1, offset index): BFS
+// layers over the tight edges with eq 33's tie rule built in.  With t*,
+// t*_j = t*_p + w_I(p -> j) for the predecessor p the key names; a node
+// whose key or t* changed pushes to its tight children, and a child that
+// the push names its predecessor again re-reads the parent's t*.  Keys only
+// decrease, t* follows the (acyclic) predecessor tree, so the fixed point
+// is the ordered fold along that tree for any schedule.
+__device__ __forceinline__ void relax_tree(const RelaxArgs& a, int round, int T) {
   extern __shared__ double smem_d[];
-  __shared__ int s_flag, s_prob, s_mask, s_cnt[3];
+  __shared__ int s_flag, s_prob, s_mask, s_cnt[3], s_cand[2];
   __shared__ unsigned long long s_key;
   __shared__ int s_npull;
   const TileCtx c = tile_begin(a, round, T, &s_flag, &s_prob, 1);
   if (!c.active) return;
-  const Smem s = carve(a, smem_d);
-  const int R = a.R, lw = a.lw, n = lw * a.lh, n_off = a.n_off;
+  const TreeSmem s = carve_tree(a, smem_d);
+  const int R = a.R, lw = a.lw, n = lw * a.lh, n_off = a.n_off, nw = a.nw;
   const ProbDev pr = a.probs[c.p];
   const JobDev jb = a.jobs[pr.job];
+  const bool fold = pr.tstar != nullptr;  // block-uniform
+  const int64_t gn = (int64_t)jb.nx * jb.nz;
+  const double* WI = jb.per_node ? jb.W : jb.W + (int64_t)kFieldI * jb.K * jb.K * n_off;
   if (threadIdx.x == 0) {
     s_mask = 0;
     s_key = kInfBits;
@@ -686,140 +784,158 @@ __device__ __forceinline__ void relax_hop(const RelaxArgs& a, int round, int T) 
     s_cnt[0] = 0;
     s_cnt[1] = 0;
     s_cnt[2] = 0;
+    s_cand[1] = 0;
   }
-  load_common(a, c, jb, s);
+  load_common(a, c, jb, s.cls, s.inq, s.off);
   for (int q = threadIdx.x; q < n; q += blockDim.x) {
     int gx = c.x0 + (q % lw) - R, gz = c.z0 + (q / lw) - R;
     bool in = gx >= 0 && gx < jb.nx && gz >= 0 && gz < jb.nz;
     int64_t g = (int64_t)gx + (int64_t)jb.nx * gz;
-    s.val[q] = in ? pr.tau[g] : INFINITY;
-    s.ival[q] = in ? pr.hop[g] : kHopUnset;
+    s.key[q] = in ? pr.key[g] : kKeyUnset;
+    s.ts[q] = (in && fold) ? pr.tstar[g] : NAN;
+    for (int w = 0; w < nw; ++w) s.om[w * n + q] = in ? pr.tight[(int64_t)w * gn + g] : 0u;
   }
-  const double* Wp = stage_w(a, jb, pr.field, s);
   __syncthreads();
   const int ml = my_node(a, c);
   long long raw = 0;
-  const int32_t orig = ml >= 0 ? s.ival[ml] : 0;
+  const unsigned long long okey = ml >= 0 ? s.key[ml] : 0ull;
+  const double ots = ml >= 0 ? s.ts[ml] : 0.0;
 
+  // t*_j from the predecessor its key names; true if t*_j changed
+  auto refold = [&](int j) -> bool {
+    const unsigned long long k = s.key[j];
+    if (k == kKeyUnset || (k >> 32) == 0ull) return false;  // unreached, or the source
+    const int o = (int)(k & 0xffffffffull);
+    const int p = j - s.off[o];
+    const double t = __dadd_rn(s.ts[p], w_pull(jb, WI, kFieldI, s.cls[p] & kClassMask,
+                                               s.cls[j] & kClassMask, o, n_off,
+                                               gnode(a, c, jb, j)));
+    if (dbits(t) == dbits(s.ts[j])) return false;
+    s.ts[j] = t;
+    return true;
+  };
+
+  // pull over the border band (or every node), then seed the source
   {
-    bool improved = false;
+    bool changed = false;
     if (ml >= 0 && pulls(a, c, ml)) {
       atomicAdd(&s_npull, 1);
-      const int kj = s.cls[ml];
-      const double tj = s.val[ml];
-      if (kj >= 0 && tj < INFINITY) {
-        const int64_t gml = gnode(a, c, jb, ml);
-        const int32_t cur = s.ival[ml];
-        int32_t best = cur;
-        if (jb.per_node) {
-          const double* wrow = jb.W + ((int64_t)pr.field * jb.nx * jb.nz + gml) * n_off;
-          for (int o0 = 0; o0 < n_off; o0 += kPullChunk) {
-            double wv[kPullChunk];
-#pragma unroll
-            for (int u = 0; u < kPullChunk; ++u) wv[u] = o0 + u < n_off ? wrow[o0 + u] : 0.0;
-#pragma unroll
-            for (int u = 0; u < kPullChunk; ++u) {
-              const int o = o0 + u;
-              if (o >= n_off) break;
-              const int ii = ml - s.off[o];
-              const int32_t hi = s.ival[ii];
-              if (s.cls[ii] < 0 || hi == kHopUnset || hi + 1 >= best) continue;
-              if (__dadd_rn(s.val[ii], wv[u]) == tj) best = hi + 1;
-            }
-          }
-        } else {
-          for (int o = 0; o < n_off; ++o) {
-            const int ii = ml - s.off[o];
-            const int ki = s.cls[ii];
-            const int32_t hi = s.ival[ii];
-            if (ki < 0 || hi == kHopUnset || hi + 1 >= best) continue;
-            if (__dadd_rn(s.val[ii],
-                          w_pull(jb, Wp, pr.field, ki & kClassMask, kj, o, n_off, gml)) == tj)
-              best = hi + 1;
-          }
-        }
-        if (best < cur) {
-          s.ival[ml] = best;
-          improved = true;
-          s.inq[ml] = 1;
-        }
+      unsigned long long best = s.key[ml];
+      for (int o = 0; o < n_off; ++o) {
+        const int ii = ml - s.off[o];
+        if (!((s.om[(o >> 5) * n + ii] >> (o & 31)) & 1u)) continue;
+        const unsigned long long ki = s.key[ii];
+        if (ki == kKeyUnset) continue;
+        const unsigned long long cand = tree_key(ki, o);
+        if (cand < best) best = cand;
       }
+      if (best < s.key[ml]) {
+        s.key[ml] = best;
+        changed = true;
+      }
+      if (fold && refold(ml)) changed = true;
+      if (changed) s.inq[ml] = 2;
     }
-    frontier_add(improved, ml, s.l0, &s_cnt[0]);
+    frontier_add(changed, ml, s.l0, &s_cnt[0]);
   }
   if (threadIdx.x == 0) {
     const int sn = seed_node(a, c, pr.src, jb.nx);
-    if (sn >= 0 && s.cls[sn] >= 0 && atomicExch(&s.inq[sn], 1) != 1)
+    if (sn >= 0 && s.cls[sn] >= 0 && atomicExch(&s.inq[sn], 2) != 2)
       s.l0[atomicAdd(&s_cnt[0], 1)] = sn;
   }
   __syncthreads();
 
+  // push levels: each frontier node walks only its tight out-edges (one
+  // lane per node, bits taken one at a time; the loop runs while any lane
+  // of the wavefront has one left)
   int ci = 0, it = 1;
   int nf = s_cnt[0];
-  const int ngroups = (n_off + G - 1) / G;
   const int nt = blockDim.x;
-  const int q_step = nt / ngroups, r_step = nt % ngroups;
   while (nf > 0 && it <= kLocalIterCap) {
     const int cn = ci == 2 ? 0 : ci + 1, cz = cn == 2 ? 0 : cn + 1;
     int32_t* const lcur = (it & 1) ? s.l0 : s.l1;
     int32_t* const lnxt = (it & 1) ? s.l1 : s.l0;
-    if (threadIdx.x == 0) s_cnt[cz] = 0;
-    raw += (long long)nf * n_off;
-    // work items = (frontier node, group of G offsets), spread over the block;
-    // every thread runs the same trip count so frontier_add sees whole waves
-    const int total = nf * ngroups;
-    const int bound = (total + nt - 1) / nt * nt;
-    int f = threadIdx.x / ngroups, g = threadIdx.x % ngroups;
-    for (int item = threadIdx.x; item < bound; item += nt) {
-      const bool live = item < total;
+    // candidate counts alternate by level: the other slot was last read
+    // before the previous level's final barrier
+    int* const cand_cnt = &s_cand[it & 1];
+    if (threadIdx.x == 0) {
+      s_cnt[cz] = 0;
+      s_cand[(it + 1) & 1] = 0;
+    }
+    const int32_t stamp = (it + 1) << 1;
+    for (int b0 = 0; b0 < nf; b0 += nt) {
+      const int f = b0 + (int)threadIdx.x;
+      const bool live = f < nf;
       const int i = live ? lcur[f] : 0;
-#pragma unroll
-      for (int u = 0; u < G; ++u) {
-        bool improved = false;
+      const unsigned long long ki = live ? s.key[i] : kKeyUnset;
+      const bool has = ki != kKeyUnset;
+      int w = 0;
+      uint32_t m = has ? s.om[i] : 0u;
+      while (true) {
+        while (m == 0u && has && ++w < nw) m = s.om[w * n + i];
+        if (__ballot(m != 0u) == 0ull) break;
+        bool mark = false;
         int jj = 0;
-        const int o = g * G + u;
-        if (live && o < n_off) {
-          const double vi = s.val[i];
-          const int32_t cand = s.ival[i] + 1;
-          const int ki = s.cls[i] & kClassMask;
-          const int64_t gi = gnode(a, c, jb, i);
-            const int j = i + s.off[o];
-            const int kj = s.cls[j];
-            if (kj >= 0 && !(kj & kHaloBit)) {
-              const double tj = s.val[j];
-              // tight edge into a reachable node (inf + w == inf is no edge)
-              if (cand < s.ival[j] && tj < INFINITY &&
-                  __dadd_rn(vi, w_push(jb, Wp, pr.field, ki, kj, o, n_off, gi)) == tj) {
-                const int32_t old = atomicMin(&s.ival[j], cand);
-                if (cand < old) {
-                  improved = atomicExch(&s.inq[j], it + 1) != it + 1;
-                  jj = j;
-                }
+        if (m != 0u) {
+          const int b = __ffs(m) - 1;
+          m &= m - 1u;
+          const int o = w * 32 + b;
+          const int j = i + s.off[o];
+          const int kj = s.cls[j];
+          ++raw;
+          if (kj >= 0 && !(kj & kHaloBit)) {
+            const unsigned long long cand = tree_key(ki, o);
+            if (cand < s.key[j] || (fold && cand == s.key[j])) {
+              const unsigned long long old = atomicMin(&s.key[j], cand);
+              if (cand < old) {
+                mark = (atomicMax(&s.inq[j], stamp | 1) >> 1) != it + 1;
+                jj = j;
+              } else if (fold && cand == old) {
+                mark = (atomicMax(&s.inq[j], stamp) >> 1) != it + 1;
+                jj = j;
               }
             }
+          }
         }
-        frontier_add(improved, jj, lnxt, &s_cnt[cn]);
-      }
-      f += q_step;
-      g += r_step;
-      if (g >= ngroups) {
-        g -= ngroups;
-        ++f;
+        if (fold) frontier_add(mark, jj, s.lc, cand_cnt);
+        else frontier_add(mark, jj, lnxt, &s_cnt[cn]);
       }
     }
     __syncthreads();
+    if (fold) {
+      // keep the candidates whose key changed or whose t* changes
+      const int nc = *cand_cnt;
+      for (int b0 = 0; b0 < nc; b0 += nt) {
+        const int q = b0 + (int)threadIdx.x;
+        const bool live = q < nc;
+        const int j = live ? s.lc[q] : 0;
+        bool keep = false;
+        if (live) {
+          const bool kchg = (s.inq[j] & 1) != 0;
+          keep = refold(j) || kchg;
+        }
+        frontier_add(keep, j, lnxt, &s_cnt[cn]);
+      }
+      __syncthreads();
+    }
     nf = s_cnt[cn];
     ci = cn;
     ++it;
   }
 
   int mask = (nf > 0) ? (1 << 4) : 0;
-  if (ml >= 0 && s.ival[ml] < orig) {
-    int x = ml % lw - R, z = ml / lw - R;
-    pr.hop[(int64_t)(c.x0 + x) + (int64_t)jb.nx * (c.z0 + z)] = s.ival[ml];
-    const int bb = border_bits(x, z, a.tx, a.tz, R);
-    mask |= bb;
-    if (bb && a.bucket > 0.0) atomicMin(&s_key, dbits((double)s.ival[ml]));
+  if (ml >= 0) {
+    const bool kc = s.key[ml] != okey;
+    const bool tc = fold && dbits(s.ts[ml]) != dbits(ots);
+    if (kc || tc) {
+      int x = ml % lw - R, z = ml / lw - R;
+      const int64_t g = (int64_t)(c.x0 + x) + (int64_t)jb.nx * (c.z0 + z);
+      if (kc) pr.key[g] = s.key[ml];
+      if (tc) pr.tstar[g] = s.ts[ml];
+      const int bb = border_bits(x, z, a.tx, a.tz, R);
+      mask |= bb;
+      if (bb && a.bucket > 0.0) atomicMin(&s_key, dbits((double)(s.key[ml] >> 32)));
+    }
   }
   count_visit(a, 1, raw + (long long)s_npull * n_off, it - 1);
   if (mask) atomicOr(&s_mask, mask);
@@ -827,193 +943,23 @@ __device__ __forceinline__ void relax_hop(const RelaxArgs& a, int round, int T) 
   if (threadIdx.x == 0 && s_mask) activate(a, round, c, pr, jb, s_mask, s_key);
 }
 
-// pred_j = tight in-neighbour with hop_j - 1 and the smallest offset index.
-// blockIdx.y = problem.
+// pred_j = j - (the offset its key names); -1 for the source and unreached
+// nodes.  blockIdx.y = problem.
 __global__ void k_pred(RelaxArgs a) {
-  const ProbDev pr = a.probs[blockIdx.y];
-  const JobDev jb = a.jobs[pr.job];
-  const int K = jb.K, n_off = a.n_off;
-  const int64_t n_nodes = (int64_t)jb.nx * jb.nz;
-  const double* Wf = jb.per_node ? jb.W : jb.W + (int64_t)pr.field * K * K * n_off;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_nodes;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t hj = pr.hop[j];
-    int32_t best = -1;
-    const int jx = (int)(j % jb.nx), jz = (int)(j / jb.nx);
-    const int32_t kj = jb.per_node ? 0 : jb.class_id[j];
-    if (j != pr.src && hj != kHopUnset && kj >= 0 && kj < K) {
-      const double tj = pr.tau[j];
-      for (int o = 0; o < n_off; ++o) {
-        int ix = jx - a.ox[o], iz = jz - a.oz[o];
-        if (ix < 0 || ix >= jb.nx || iz < 0 || iz >= jb.nz) continue;
-        int64_t i = (int64_t)ix + (int64_t)jb.nx * iz;
-        if (pr.hop[i] != hj - 1) continue;
-        int32_t ki = jb.per_node ? 0 : jb.class_id[i];
-        if (ki < 0 || ki >= K) continue;
-        if (__dadd_rn(pr.tau[i], w_pull(jb, Wf, pr.field, ki, kj, o, n_off, j)) == tj) {
-          best = (int32_t)i;
-          break;
-        }
-      }
-    }
-    if (pr.pred) pr.pred[j] = best;
-  }
-}
-
-// Separate pass (after every hop read): hop[] := predecessor offset index.
-__global__ void k_pred_offsets(RelaxArgs a) {
   const ProbDev pr = a.probs[blockIdx.y];
   if (!pr.pred) return;
   const JobDev jb = a.jobs[pr.job];
-  const int64_t n_nodes = (int64_t)jb.nx * jb.nz;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_nodes;
+  const int64_t n = (int64_t)jb.nx * jb.nz;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * blockDim.x) {
-    int32_t i = pr.pred[j];
-    int32_t o_idx = -1;
-    if (i >= 0) {
-      int dx = (int)(j % jb.nx) - (int)(i % jb.nx), dz = (int)(j / jb.nx) - (int)(i / jb.nx);
-      for (int o = 0; o < a.n_off; ++o)
-        if (a.ox[o] == dx && a.oz[o] == dz) {
-          o_idx = o;
-          break;
-        }
+    const unsigned long long k = pr.key[j];
+    int32_t p = -1;
+    if (k != kKeyUnset && (k >> 32) != 0ull) {
+      const int o = (int)(k & 0xffffffffull);
+      p = (int32_t)(j - (a.ox[o] + (int64_t)jb.nx * a.oz[o]));
     }
-    pr.hop[j] = o_idx;
+    pr.pred[j] = p;
   }
-}
-
-// Phase TSTAR: t*_j = t*_pred + w_I(pred -> j) once t*_pred is known; a
-// node whose value became known pushes to the children naming it as their
-// predecessor.
-template <int G>
-__device__ __forceinline__ void relax_tstar(const RelaxArgs& a, int round, int T) {
-  extern __shared__ double smem_d[];
-  __shared__ int s_flag, s_prob, s_mask, s_cnt[3];
-  __shared__ unsigned long long s_key;
-  __shared__ int s_npull;
-  const TileCtx c = tile_begin(a, round, T, &s_flag, &s_prob, 2);
-  if (!c.active) return;
-  const Smem s = carve(a, smem_d);
-  const int R = a.R, lw = a.lw, n = lw * a.lh, n_off = a.n_off;
-  const ProbDev pr = a.probs[c.p];
-  if (!pr.tstar) return;  // block-uniform
-  const JobDev jb = a.jobs[pr.job];
-  if (threadIdx.x == 0) {
-    s_mask = 0;
-    s_key = kInfBits;
-    s_npull = 0;
-    s_cnt[0] = 0;
-    s_cnt[1] = 0;
-    s_cnt[2] = 0;
-  }
-  load_common(a, c, jb, s);
-  for (int q = threadIdx.x; q < n; q += blockDim.x) {
-    int gx = c.x0 + (q % lw) - R, gz = c.z0 + (q / lw) - R;
-    bool in = gx >= 0 && gx < jb.nx && gz >= 0 && gz < jb.nz;
-    int64_t g = (int64_t)gx + (int64_t)jb.nx * gz;
-    s.val[q] = in ? pr.tstar[g] : NAN;
-    // predecessor offset index of interior nodes (children); -1 elsewhere
-    bool inter = (q % lw) >= R && (q % lw) < R + c.txe && (q / lw) >= R && (q / lw) < R + c.tze;
-    s.ival[q] = inter ? pr.hop[g] : -1;
-  }
-  const double* WI = stage_w(a, jb, kFieldI, s);
-  __syncthreads();
-  const int ml = my_node(a, c);
-  long long raw = 0;
-
-  {
-    bool known = false;
-    if (ml >= 0 && pulls(a, c, ml)) {
-      atomicAdd(&s_npull, 1);
-      const int o = s.ival[ml];
-      if (o >= 0 && isnan(s.val[ml])) {
-        const int ii = ml - s.off[o];
-        const double tp = s.val[ii];
-        if (!isnan(tp)) {
-          s.val[ml] = __dadd_rn(tp, w_pull(jb, WI, kFieldI, s.cls[ii] & kClassMask, s.cls[ml],
-                                           o, n_off, gnode(a, c, jb, ml)));
-          known = true;
-        }
-      }
-    }
-    frontier_add(known, ml, s.l0, &s_cnt[0]);
-  }
-  if (threadIdx.x == 0) {
-    const int sn = seed_node(a, c, pr.src, jb.nx);
-    if (sn >= 0 && s.cls[sn] >= 0 && atomicExch(&s.inq[sn], 1) != 1)
-      s.l0[atomicAdd(&s_cnt[0], 1)] = sn;
-  }
-  __syncthreads();
-
-  int ci = 0, it = 1;
-  int nf = s_cnt[0];
-  const int ngroups = (n_off + G - 1) / G;
-  const int nt = blockDim.x;
-  const int q_step = nt / ngroups, r_step = nt % ngroups;
-  while (nf > 0 && it <= kLocalIterCap) {
-    const int cn = ci == 2 ? 0 : ci + 1, cz = cn == 2 ? 0 : cn + 1;
-    int32_t* const lcur = (it & 1) ? s.l0 : s.l1;
-    int32_t* const lnxt = (it & 1) ? s.l1 : s.l0;
-    if (threadIdx.x == 0) s_cnt[cz] = 0;
-    raw += (long long)nf * n_off;
-    // work items = (frontier node, group of G offsets), spread over the block;
-    // every thread runs the same trip count so frontier_add sees whole waves
-    const int total = nf * ngroups;
-    const int bound = (total + nt - 1) / nt * nt;
-    int f = threadIdx.x / ngroups, g = threadIdx.x % ngroups;
-    for (int item = threadIdx.x; item < bound; item += nt) {
-      const bool live = item < total;
-      const int i = live ? lcur[f] : 0;
-#pragma unroll
-      for (int u = 0; u < G; ++u) {
-        bool improved = false;
-        int jj = 0;
-        const int o = g * G + u;
-        if (live && o < n_off) {
-          const double vi = s.val[i];
-          const int ki = s.cls[i] & kClassMask;
-          const int64_t gi = gnode(a, c, jb, i);
-            const int j = i + s.off[o];
-            // j's predecessor is i (j - i = o; only interior nodes carry one).
-            // One parent per child, so one writer; the NaN test skips
-            // children the pull already resolved.
-            if (s.ival[j] == o && isnan(s.val[j])) {
-              s.val[j] = __dadd_rn(
-                  vi, w_push(jb, WI, kFieldI, ki, s.cls[j] & kClassMask, o, n_off, gi));
-              improved = true;
-              jj = j;
-            }
-        }
-        frontier_add(improved, jj, lnxt, &s_cnt[cn]);
-      }
-      f += q_step;
-      g += r_step;
-      if (g >= ngroups) {
-        g -= ngroups;
-        ++f;
-      }
-    }
-    __syncthreads();
-    nf = s_cnt[cn];
-    ci = cn;
-    ++it;
-  }
-
-  int mask = (nf > 0) ? (1 << 4) : 0;
-  if (ml >= 0 && s.ival[ml] >= 0 && !isnan(s.val[ml])) {
-    int x = ml % lw - R, z = ml / lw - R;
-    int64_t g = (int64_t)(c.x0 + x) + (int64_t)jb.nx * (c.z0 + z);
-    if (isnan(pr.tstar[g])) {
-      pr.tstar[g] = s.val[ml];
-      const int bb = border_bits(x, z, a.tx, a.tz, R);
-      mask |= bb;
-      if (bb && a.bucket > 0.0) atomicMin(&s_key, dbits(s.val[ml]));
-    }
-  }
-  count_visit(a, 2, raw + s_npull, it - 1);
-  if (mask) atomicOr(&s_mask, mask);
-  __syncthreads();
-  if (threadIdx.x == 0 && s_mask) activate(a, round, c, pr, jb, s_mask, s_key);
 }
 
 // One launch per round.  With one workgroup per tile (grid = n_tiles) tile T
@@ -1024,8 +970,7 @@ __device__ __forceinline__ void relax_tstar(const RelaxArgs& a, int round, int T
 template <int G, int PH>
 __device__ __forceinline__ void visit(const RelaxArgs& a, int round, int T) {
   if constexpr (PH == 0) relax_tau<G>(a, round, T);
-  else if constexpr (PH == 1) relax_hop<G>(a, round, T);
-  else relax_tstar<G>(a, round, T);
+  else relax_tree(a, round, T);
 }
 template <int G, int PH>
 __device__ __forceinline__ void round_tiles(const RelaxArgs& a, int round) {
@@ -1045,13 +990,8 @@ template <int G>
 __global__ void __launch_bounds__(kRelaxThreads) k_relax_tau(RelaxArgs a, int round) {
   round_tiles<G, 0>(a, round);
 }
-template <int G>
-__global__ void __launch_bounds__(kRelaxThreads) k_relax_hop(RelaxArgs a, int round) {
-  round_tiles<G, 1>(a, round);
-}
-template <int G>
-__global__ void __launch_bounds__(kRelaxThreads) k_relax_tstar(RelaxArgs a, int round) {
-  round_tiles<G, 2>(a, round);
+__global__ void __launch_bounds__(kRelaxThreads) k_relax_tree(RelaxArgs a, int round) {
+  round_tiles<1, 1>(a, round);
 }
 
 // ------------------------------------------------- persistent launch ---
@@ -1117,8 +1057,7 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_persist(RelaxArgs a, Pe
     for (int i = blockIdx.x; i < n_act; i += gridDim.x) {
       const int T = lst[i];
       if constexpr (PH == 0) relax_tau<G>(a, round, T);
-      else if constexpr (PH == 1) relax_hop<G>(a, round, T);
-      else relax_tstar<G>(a, round, T);
+      else relax_tree(a, round, T);
       __syncthreads();  // LDS is reused by the next tile
     }
     if (!grid_barrier(p)) {
@@ -1174,7 +1113,7 @@ static int problems_per_source(uint32_t outs) {
 }
 
 struct Plan {
-  int tx, tz, R, n_off, lw, lh;
+  int tx, tz, R, n_off, lw, lh, nw;
   int n_prob = 0;
   int64_t n_tiles = 0;
   int max_rounds = 0;
@@ -1182,7 +1121,7 @@ struct Plan {
   std::vector<int> ntx, ntz, K;
   size_t off_star = 0, off_lbin = 0, off_jobs = 0, off_probs = 0, off_flags = 0, off_list = 0,
          off_counter = 0, off_key = 0, off_pmin = 0, off_wmin = 0,
-         off_err = 0, off_hop = 0, total = 0;
+         off_err = 0, off_nkey = 0, off_tight = 0, total = 0;
   std::vector<size_t> off_W;  // per job
   int w_lds_doubles = 0;
 };
@@ -1256,10 +1195,12 @@ static int make_plan(const chert_trace_job* jobs, int n_jobs, const chert_trace_
   if (P->tx < P->R || P->tz < P->R || P->tx * P->tz > kRelaxThreads)
     return fail(CHERT_ERR_INVALID_ARG, "tile must be >= radius per side and <= 1024 nodes");
   P->n_off = star_2d(P->R, 1.0, 1.0, 4, nullptr, nullptr, nullptr, nullptr);
+  P->nw = (P->n_off + 31) / 32;
   P->lw = P->tx + 2 * P->R;
   P->lh = P->tz + 2 * P->R;
   const int per = problems_per_source(o->outputs);
-  int64_t max_tile_span = 0, prob_nodes = 0;
+  int64_t max_tile_span = 0, tree_nodes = 0;
+  const int tree_per = ((o->outputs & CHERT_OUT_PRED_P) ? 1 : 0) + ((o->outputs & CHERT_OUT_PRED_A) ? 1 : 0);
   int w_lds = 0;
   for (int j = 0; j < n_jobs; ++j) {
     const chert_grid* g = jobs[j].g;
@@ -1271,7 +1212,7 @@ static int make_plan(const chert_trace_job* jobs, int n_jobs, const chert_trace_
     int np = per * jobs[j].n_src;
     P->n_prob += np;
     P->n_tiles += (int64_t)np * ntx * ntz;
-    prob_nodes += (int64_t)np * g->nx * g->nz;
+    tree_nodes += (int64_t)tree_per * jobs[j].n_src * g->nx * g->nz;
     if (ntx + ntz > max_tile_span) max_tile_span = ntx + ntz;
     if (g->class_id_dev) {
       size_t wf = (size_t)jobs[j].n_classes * jobs[j].n_classes * P->n_off * sizeof(double);
@@ -1316,8 +1257,10 @@ static int make_plan(const chert_trace_job* jobs, int n_jobs, const chert_trace_
                             : (size_t)jobs[j].g->nx * jobs[j].g->nz;
     off += align256((size_t)2 * rows * P->n_off * sizeof(double));
   }
-  P->off_hop = off;
-  off += align256((size_t)prob_nodes * sizeof(int32_t));
+  P->off_nkey = off;
+  off += align256((size_t)tree_nodes * sizeof(unsigned long long));
+  P->off_tight = off;
+  off += align256((size_t)tree_nodes * P->nw * sizeof(uint32_t));
   P->total = off;
   return CHERT_OK;
 }
@@ -1351,16 +1294,13 @@ typedef void (*PersistKern)(RelaxArgs, PersistArgs);
 
 static RoundKern round_kernel(int ph, int G) {
   if (ph == 0) return G == 1 ? k_relax_tau<1> : (G == 2 ? k_relax_tau<2> : k_relax_tau<4>);
-  if (ph == 1) return G == 1 ? k_relax_hop<1> : (G == 2 ? k_relax_hop<2> : k_relax_hop<4>);
-  return G == 1 ? k_relax_tstar<1> : (G == 2 ? k_relax_tstar<2> : k_relax_tstar<4>);
+  return k_relax_tree;  // one lane per frontier node: no push groups
 }
 
 static PersistKern persist_kernel(int ph, int G) {
   if (ph == 0)
     return G == 1 ? k_relax_persist<1, 0> : (G == 2 ? k_relax_persist<2, 0> : k_relax_persist<4, 0>);
-  if (ph == 1)
-    return G == 1 ? k_relax_persist<1, 1> : (G == 2 ? k_relax_persist<2, 1> : k_relax_persist<4, 1>);
-  return G == 1 ? k_relax_persist<1, 2> : (G == 2 ? k_relax_persist<2, 2> : k_relax_persist<4, 2>);
+  return k_relax_persist<1, 1>;  // tree phase: no push groups
 }
 
 // Persistent-launch grid: as many workgroups as the device holds at once
@@ -1384,7 +1324,7 @@ struct Prepared {
   Plan P;
   RelaxArgs a{};
   PersistArgs pa{};
-  size_t lds = 0;
+  size_t lds[2] = {0, 0};  // dynamic LDS per phase (tau, tree)
   uint8_t* ws = nullptr;
   JobDev* djobs = nullptr;
   ProbDev* dprobs = nullptr;
@@ -1393,8 +1333,8 @@ struct Prepared {
   int32_t* doz = nullptr;
   double* dL = nullptr;
   int32_t* dcol = nullptr;
-  int pgrid[3] = {0, 0, 0};  // persistent-launch grid per phase
-  int rgrid[3] = {0, 0, 0};  // per-round launch grid per phase
+  int pgrid[2] = {0, 0};  // persistent-launch grid per phase
+  int rgrid[2] = {0, 0};  // per-round launch grid per phase
   bool fixed_rounds = false;  // per-round launches without host checks (graphs)
 };
 
@@ -1433,8 +1373,9 @@ static int prepare(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
   std::vector<JobDev>& jd = Q->jd;
   jd.assign(n_jobs, JobDev{});
   std::vector<ProbDev> probs;
-  int32_t* hop = (int32_t*)(ws + P.off_hop);
-  int64_t hop_off = 0;
+  unsigned long long* nkey = (unsigned long long*)(ws + P.off_nkey);
+  uint32_t* tight = (uint32_t*)(ws + P.off_tight);
+  int64_t tree_off = 0;  // nodes of the tree-phase problems so far
   int tile_base = 0;
   for (int j = 0; j < n_jobs; ++j) {
     const chert_trace_job& J = jobs[j];
@@ -1461,8 +1402,11 @@ static int prepare(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
         p.job = j;
         p.field = kFieldR;
         p.tile_base = tile_base;
-        p.hop = hop + hop_off;
-        hop_off += n;
+        if (p.pred) {
+          p.key = nkey + tree_off;
+          p.tight = tight + tree_off * P.nw;
+          tree_off += n;
+        }
         tile_base += ntiles;
         probs.push_back(p);
       }
@@ -1475,8 +1419,11 @@ static int prepare(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
         p.job = j;
         p.field = kFieldI;
         p.tile_base = tile_base;
-        p.hop = hop + hop_off;
-        hop_off += n;
+        if (p.pred) {
+          p.key = nkey + tree_off;
+          p.tight = tight + tree_off * P.nw;
+          tree_off += n;
+        }
         tile_base += ntiles;
         probs.push_back(p);
       }
@@ -1500,6 +1447,7 @@ static int prepare(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
   a.tz = P.tz;
   a.R = P.R;
   a.n_off = P.n_off;
+  a.nw = P.nw;
   a.lw = P.lw;
   a.lh = P.lh;
   a.n_prob = P.n_prob;
@@ -1518,7 +1466,8 @@ static int prepare(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
   a.pmin = (unsigned long long*)(ws + P.off_pmin);
   a.wmin = (const double*)(ws + P.off_wmin);
   a.bucket = o->bucket_width;
-  Q->lds = lds_bytes(P.lw, P.lh, P.w_lds_doubles, P.n_off, P.tx, P.tz);
+  Q->lds[0] = lds_bytes(P.lw, P.lh, P.w_lds_doubles, P.n_off, P.tx, P.tz);
+  Q->lds[1] = tree_lds_bytes(P.lw, P.lh, P.nw, P.n_off, P.tx, P.tz);
   Q->pa.max_rounds = P.max_rounds;
   Q->pa.bar = (uint32_t*)(ws + P.off_err + 192);
   Q->pa.result = (int32_t*)(ws + P.off_err + 208);
@@ -1530,12 +1479,12 @@ static int prepare(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
   Q->dL = dL;
   Q->dcol = dcol;
   const int G = o->push_group ? o->push_group : 2;
-  for (int ph = 0; ph < 3; ++ph) {
+  for (int ph = 0; ph < 2; ++ph) {
     if (o->launch == CHERT_LAUNCH_PERSISTENT)
-      rc = persist_grid((const void*)persist_kernel(ph, G), tile_threads(P.tx, P.tz), Q->lds,
+      rc = persist_grid((const void*)persist_kernel(ph, G), tile_threads(P.tx, P.tz), Q->lds[ph],
                         P.n_tiles, &Q->pgrid[ph]);
     else
-      rc = persist_grid((const void*)round_kernel(ph, G), tile_threads(P.tx, P.tz), Q->lds,
+      rc = persist_grid((const void*)round_kernel(ph, G), tile_threads(P.tx, P.tz), Q->lds[ph],
                         P.n_tiles, &Q->rgrid[ph]);
     if (rc) return rc;
     // per-round launches: one workgroup per tile while that is at most 4x
@@ -1558,7 +1507,6 @@ static int enqueue(const Prepared& Q, const chert_trace_job* jobs, int n_jobs,
   const PersistArgs& pa = Q.pa;
   uint8_t* ws = Q.ws;
   const uint32_t outs = o->outputs;
-  const size_t lds = Q.lds;
   for (int j = 0; j < n_jobs; ++j) {
     const chert_trace_job& J = jobs[j];
     chert_cache_layout lay;
@@ -1599,20 +1547,20 @@ static int enqueue(const Prepared& Q, const chert_trace_job* jobs, int n_jobs,
   CHERT_LAUNCH("k_init_fields", k_init_fields, pgrid, dim3(256), 0, s, Q.dprobs, Q.djobs, a.err,
                a.stats, pa.result);
   const int64_t n_flags = 2 * P.n_tiles;
-  auto init_flags = [&](int tstar_phase) {
+  auto init_flags = [&](int tree_phase) {
     CHERT_LAUNCH("k_clear_flags", k_clear_flags, dim3(256), dim3(256), 0, s, a.flags, n_flags,
                  a.counter, P.max_rounds + 2, pa.bar, a.key, 2 * P.n_tiles, a.pmin,
                  3 * P.n_prob);
     CHERT_LAUNCH("k_seed_flags", k_seed_flags, dim3((P.n_prob + 63) / 64), dim3(64), 0, s,
                  a.flags, a.list, a.counter, Q.dprobs, Q.djobs, P.n_prob, P.tx, P.tz,
-                 tstar_phase, a.key, a.pmin);
+                 tree_phase, a.key, a.pmin);
   };
   const int G = o->push_group ? o->push_group : 2;
-  static const char* kname[3] = {"k_relax_tau", "k_relax_hop", "k_relax_tstar"};
-  static const char* pname[3] = {"k_relax_persist_tau", "k_relax_persist_hop",
-                                 "k_relax_persist_tstar"};
+  static const char* kname[2] = {"k_relax_tau", "k_relax_tree"};
+  static const char* pname[2] = {"k_relax_persist_tau", "k_relax_persist_tree"};
   auto phase = [&](int ph) -> int {
-    init_flags(ph == 2 ? 1 : 0);
+    const size_t lds = Q.lds[ph];
+    init_flags(ph);
     if (o->launch == CHERT_LAUNCH_PERSISTENT) {
       CHERT_LAUNCH(pname[ph], persist_kernel(ph, G), dim3((unsigned)Q.pgrid[ph]),
                    dim3((unsigned)tile_threads(a.tx, a.tz)), lds, s, a, pa);
@@ -1634,15 +1582,12 @@ static int enqueue(const Prepared& Q, const chert_trace_job* jobs, int n_jobs,
   int rc = phase(0);
   if (rc) return rc;
   if (outs & (CHERT_OUT_PRED_P | CHERT_OUT_PRED_A)) {
+    CHERT_LAUNCH("k_tight_out", k_tight_out, pgrid, dim3(256), 0, s, a);
     rc = phase(1);
     if (rc) return rc;
     CHERT_LAUNCH("k_pred", k_pred, pgrid, dim3(256), 0, s, a);
-    CHERT_LAUNCH("k_pred_offsets", k_pred_offsets, pgrid, dim3(256), 0, s, a);
-  }
-  if (outs & CHERT_OUT_TSTAR) {
-    rc = phase(2);
-    if (rc) return rc;
-    CHERT_LAUNCH("k_tstar_finish", k_tstar_finish, pgrid, dim3(256), 0, s, Q.dprobs, Q.djobs);
+    if (outs & CHERT_OUT_TSTAR)
+      CHERT_LAUNCH("k_tstar_finish", k_tstar_finish, pgrid, dim3(256), 0, s, Q.dprobs, Q.djobs);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
@@ -1664,8 +1609,7 @@ static int finish(const Prepared& Q, const chert_trace_opts* o, hipStream_t s, i
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
   const uint32_t outs = o->outputs;
-  const bool ran[3] = {true, (outs & (CHERT_OUT_PRED_P | CHERT_OUT_PRED_A)) != 0,
-                       (outs & CHERT_OUT_TSTAR) != 0};
+  const bool ran[3] = {true, (outs & (CHERT_OUT_PRED_P | CHERT_OUT_PRED_A)) != 0, false};
   int status = CHERT_OK;
   if (o->launch == CHERT_LAUNCH_PERSISTENT || Q.fixed_rounds)
     for (int ph = 0; ph < 3; ++ph) {
