@@ -468,6 +468,31 @@ __device__ __forceinline__ void frontier_add(bool flag, int node, int32_t* list,
 
 
 
+// frontier_add for G flags per lane: one LDS atomic per wavefront for all.
+template <int G>
+__device__ __forceinline__ void frontier_add_n(const bool* flag, const int* node, int32_t* list,
+                                               int* count) {
+  unsigned long long b[G];
+  int tot = 0;
+#pragma unroll
+  for (int u = 0; u < G; ++u) {
+    b[u] = __ballot(flag[u]);
+    tot += __popcll(b[u]);
+  }
+  if (tot == 0) return;
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)__ballot(true)) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(count, tot);
+  base = __shfl(base, leader);
+  const unsigned long long lt = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int u = 0; u < G; ++u) {
+    if (flag[u]) list[base + __popcll(b[u] & lt)] = node[u];
+    base += __popcll(b[u]);
+  }
+}
+
 // Does this visit pull node ml (LDS index)?  The R-wide strips facing the
 // neighbours whose halo part changed (side bits), or all on kFlagFull.
 __device__ __forceinline__ bool pulls(const RelaxArgs& a, const TileCtx& c, int ml) {
@@ -600,52 +625,122 @@ __device__ __forceinline__ void relax_tau(const RelaxArgs& a, int round, int T) 
   int nf = s_cnt[0];
   const int ngroups = (n_off + G - 1) / G;
   const int nt = blockDim.x;
+  // Work items = (frontier node, group of G offsets).  When the block
+  // holds whole groups, each thread keeps one group for the whole visit
+  // (its star offsets in registers) and walks the frontier in steps of
+  // `per` nodes; otherwise the items rotate over the block.
+  const int per = nt / ngroups;
+  const int my_g = per > 0 ? (int)threadIdx.x % ngroups : 0;
+  const int my_f = per > 0 ? (int)threadIdx.x / ngroups : 0;
+  int offr[G];
+#pragma unroll
+  for (int u = 0; u < G; ++u) {
+    const int o = my_g * G + u;
+    offr[u] = o < n_off ? s.off[o] : 0;
+  }
   const int q_step = nt / ngroups, r_step = nt % ngroups;
-  while (nf > 0 && it <= kLocalIterCap) {
-    const int cn = ci == 2 ? 0 : ci + 1, cz = cn == 2 ? 0 : cn + 1;
-    int32_t* const lcur = (it & 1) ? s.l0 : s.l1;
-    int32_t* const lnxt = (it & 1) ? s.l1 : s.l0;
-    if (threadIdx.x == 0) s_cnt[cz] = 0;
-    raw += (long long)nf * n_off;
-    // work items = (frontier node, group of G offsets), spread over the block;
-    // every thread runs the same trip count so frontier_add sees whole waves
-    const int total = nf * ngroups;
-    const int bound = (total + nt - 1) / nt * nt;
-    int f = threadIdx.x / ngroups, g = threadIdx.x % ngroups;
-    for (int item = threadIdx.x; item < bound; item += nt) {
-      const bool live = item < total;
-      const int i = live ? lcur[f] : 0;
+
+  // one item; "plain read first": most pushes do not improve and skip
+  // the atomic.  Per-node weights: every load of the G edges first
+  // (independent chains in flight together), then the atomics, then one
+  // append for all of them.
+  auto push_item = [&](bool live, int i, int g, const int* offs, int32_t* lnxt, int* cnt) {
+    const double vi = s.val[i];
+    const int ki0 = s.cls[i];
+    const int ki = ki0 >= 0 ? (ki0 & kClassMask) : 0;
+    const int64_t gi = gnode(a, c, jb, i);
+    if (!jb.per_node) {
+      // class-pair weights in LDS: edge by edge (measured faster here than
+      // batching the loads, which adds live registers)
 #pragma unroll
       for (int u = 0; u < G; ++u) {
         bool improved = false;
         int jj = 0;
         const int o = g * G + u;
         if (live && o < n_off) {
-          const double vi = s.val[i];
-          const int ki = s.cls[i] & kClassMask;
-          const int64_t gi = gnode(a, c, jb, i);
-            const int j = i + s.off[o];
-            const int kj = s.cls[j];
-            if (kj >= 0 && !(kj & kHaloBit)) {
-              const double cand = __dadd_rn(vi, w_push(jb, Wp, pr.field, ki, kj, o, n_off, gi));
-              // plain read first: most pushes do not improve, skip their atomic
-              if (cand < s.val[j]) {
-                const unsigned long long old =
-                    atomicMin((unsigned long long*)&s.val[j], dbits(cand));
-                if (dbits(cand) < old) {
-                  improved = atomicExch(&s.inq[j], it + 1) != it + 1;
-                  jj = j;
-                }
+          const int j = i + offs[u];
+          const int kj = s.cls[j];
+          if (kj >= 0 && !(kj & kHaloBit)) {
+            const double cand = __dadd_rn(vi, Wp[(ki * jb.K + kj) * n_off + o]);
+            if (cand < s.val[j]) {
+              const unsigned long long old =
+                  atomicMin((unsigned long long*)&s.val[j], dbits(cand));
+              if (dbits(cand) < old) {
+                improved = atomicExch(&s.inq[j], it + 1) != it + 1;
+                jj = j;
               }
             }
+          }
         }
-        frontier_add(improved, jj, lnxt, &s_cnt[cn]);
+        frontier_add(improved, jj, lnxt, cnt);
       }
-      f += q_step;
-      g += r_step;
-      if (g >= ngroups) {
-        g -= ngroups;
-        ++f;
+      return;
+    }
+    // per-node weights from HBM: the G loads go out together
+    int jv[G];
+    double cv[G];
+    bool tv[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int o = g * G + u;
+      jv[u] = 0;
+      cv[u] = 0.0;
+      tv[u] = false;
+      if (live && o < n_off) {
+        const int j = i + offs[u];
+        const int kj = s.cls[j];
+        if (kj >= 0 && !(kj & kHaloBit)) {
+          const double cand = __dadd_rn(vi, w_push(jb, Wp, pr.field, ki, kj, o, n_off, gi));
+          jv[u] = j;
+          cv[u] = cand;
+          tv[u] = cand < s.val[j];
+        }
+      }
+    }
+    bool imp[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      imp[u] = false;
+      if (tv[u]) {
+        const unsigned long long old =
+            atomicMin((unsigned long long*)&s.val[jv[u]], dbits(cv[u]));
+        if (dbits(cv[u]) < old) imp[u] = atomicExch(&s.inq[jv[u]], it + 1) != it + 1;
+      }
+    }
+    frontier_add_n<G>(imp, jv, lnxt, cnt);
+  };
+
+  while (nf > 0 && it <= kLocalIterCap) {
+    const int cn = ci == 2 ? 0 : ci + 1, cz = cn == 2 ? 0 : cn + 1;
+    int32_t* const lcur = (it & 1) ? s.l0 : s.l1;
+    int32_t* const lnxt = (it & 1) ? s.l1 : s.l0;
+    if (threadIdx.x == 0) s_cnt[cz] = 0;
+    raw += (long long)nf * n_off;
+    const int idle = R * lw + R;  // idle lanes stand on the first interior node
+    // every thread runs the same trip count so the appends see whole waves
+    if (per > 0) {
+      const int sweeps = (nf + per - 1) / per;
+      for (int sw = 0; sw < sweeps; ++sw) {
+        const int f = sw * per + my_f;
+        const bool live = my_f < per && f < nf;
+        push_item(live, live ? lcur[f] : idle, my_g, offr, lnxt, &s_cnt[cn]);
+      }
+    } else {
+      const int total = nf * ngroups;
+      const int bound = (total + nt - 1) / nt * nt;
+      int f = threadIdx.x / ngroups, g = threadIdx.x % ngroups;
+      for (int item = threadIdx.x; item < bound; item += nt) {
+        const bool live = item < total;
+        int offs[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) offs[u] = g * G + u < n_off ? s.off[g * G + u] : 0;
+        push_item(live, live ? lcur[f] : idle, g, offs, lnxt, &s_cnt[cn]);
+        f += q_step;
+        g += r_step;
+        if (g >= ngroups) {
+          g -= ngroups;
+          ++f;
+        }
       }
     }
     __syncthreads();
