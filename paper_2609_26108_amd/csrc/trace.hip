@@ -768,38 +768,89 @@ __device__ __forceinline__ void relax_tau(const RelaxArgs& a, int round, int T) 
 // is set when j = i + o lies in the grid, both classes are valid, tau_j is
 // finite and tau_i + w_ij == tau_j (eq 33's candidate set).  The set never
 // changes afterwards, so the tree phase reads neither tau nor w_R again.
-// Layout [problem][word][node].  blockIdx.y = problem.
-__global__ void k_tight_out(RelaxArgs a) {
-  const ProbDev pr = a.probs[blockIdx.y];
-  if (!pr.pred) return;
-  const JobDev jb = a.jobs[pr.job];
-  const int n_off = a.n_off, nw = a.nw;
-  const int64_t n = (int64_t)jb.nx * jb.nz;
-  const double* Wf = jb.per_node ? jb.W : jb.W + (int64_t)pr.field * jb.K * jb.K * n_off;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int ix = (int)(i % jb.nx), iz = (int)(i / jb.nx);
-    const int32_t ki = jb.per_node ? 0 : jb.class_id[i];
-    const double ti = pr.tau[i];
-    const bool ok = ki >= 0 && ki < jb.K && ti < INFINITY;
-    for (int w = 0; w < nw; ++w) {
-      uint32_t m = 0u;
-      for (int b = 0; ok && b < 32; ++b) {
-        const int o = w * 32 + b;
-        if (o >= n_off) break;
-        const int jx = ix + a.ox[o], jz = iz + a.oz[o];
-        if (jx < 0 || jx >= jb.nx || jz < 0 || jz >= jb.nz) continue;
-        const int64_t j = (int64_t)jx + (int64_t)jb.nx * jz;
-        const int32_t kj = jb.per_node ? 0 : jb.class_id[j];
-        if (kj < 0 || kj >= jb.K) continue;
-        const double tj = pr.tau[j];
-        if (tj < INFINITY &&
-            __dadd_rn(ti, w_push(jb, Wf, pr.field, ki, kj, o, n_off, i)) == tj)
-          m |= 1u << b;
-      }
-      pr.tight[(int64_t)w * n + i] = m;
+// Layout [problem][word][node].  One workgroup per (problem, tile), tau and
+// class ids of tile + halo staged in LDS (and the class-pair table when it
+// fits), one thread per interior node; problems without predecessors leave.
+__global__ void __launch_bounds__(kRelaxThreads) k_tight_out(RelaxArgs a) {
+  extern __shared__ double smem_d[];
+  __shared__ int s_prob;
+  const int T = blockIdx.x;
+  if (threadIdx.x == 0) {
+    int lo = 0, hi = a.n_prob - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.probs[mid].tile_base <= T) lo = mid;
+      else hi = mid - 1;
     }
+    s_prob = lo;
   }
+  __syncthreads();
+  const ProbDev pr = a.probs[s_prob];
+  if (!pr.pred) return;  // block-uniform
+  const JobDev jb = a.jobs[pr.job];
+  const int R = a.R, lw = a.lw, n = lw * a.lh, n_off = a.n_off, nw = a.nw;
+  const int t = T - pr.tile_base;
+  TileCtx c;
+  c.p = s_prob;
+  c.t = t;
+  c.tx = t % jb.ntx;
+  c.tz = t / jb.ntx;
+  c.x0 = c.tx * a.tx;
+  c.z0 = c.tz * a.tz;
+  c.txe = min(a.tx, jb.nx - c.x0);
+  c.tze = min(a.tz, jb.nz - c.z0);
+  c.active = 1;
+  const int w_lds = (!jb.per_node && jb.w_in_lds) ? jb.K * jb.K * n_off : 0;
+  double* Ws = smem_d;
+  double* val = Ws + a.w_lds_doubles;
+  int32_t* cls = (int32_t*)(val + n);
+  int32_t* off = cls + n;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    const int gx = c.x0 + (q % lw) - R, gz = c.z0 + (q / lw) - R;
+    double v = INFINITY;
+    int32_t k = -1;
+    if (gx >= 0 && gx < jb.nx && gz >= 0 && gz < jb.nz) {
+      const int64_t g = (int64_t)gx + (int64_t)jb.nx * gz;
+      v = pr.tau[g];
+      k = jb.per_node ? 0 : jb.class_id[g];
+      if (k < 0 || k >= jb.K) k = -1;
+    }
+    val[q] = v;
+    cls[q] = k;
+  }
+  for (int o = threadIdx.x; o < n_off; o += blockDim.x) off[o] = a.ox[o] + a.oz[o] * lw;
+  const double* Wp = jb.per_node ? jb.W : jb.W + (int64_t)pr.field * jb.K * jb.K * n_off;
+  if (w_lds) {
+    for (int q = threadIdx.x; q < w_lds; q += blockDim.x) Ws[q] = Wp[q];
+    Wp = Ws;
+  }
+  __syncthreads();
+  const int ml = my_node(a, c);
+  if (ml < 0) return;
+  const int ki = cls[ml];
+  const double ti = val[ml];
+  const bool ok = ki >= 0 && ti < INFINITY;
+  const int64_t gi = gnode(a, c, jb, ml);
+  const int64_t gn = (int64_t)jb.nx * jb.nz;
+  for (int w = 0; w < nw; ++w) {
+    uint32_t m = 0u;
+    for (int b = 0; ok && b < 32; ++b) {
+      const int o = w * 32 + b;
+      if (o >= n_off) break;
+      const int j = ml + off[o];
+      const int kj = cls[j];
+      if (kj < 0) continue;
+      const double tj = val[j];
+      if (tj < INFINITY && __dadd_rn(ti, w_push(jb, Wp, pr.field, ki, kj, o, n_off, gi)) == tj)
+        m |= 1u << b;
+    }
+    pr.tight[(int64_t)w * gn + gi] = m;
+  }
+}
+
+static size_t tight_lds_bytes(int lw, int lh, int w_doubles, int n_off) {
+  const size_t n = (size_t)lw * lh;
+  return sizeof(double) * (w_doubles + n) + sizeof(int32_t) * (n + n_off);
 }
 
 // key of j when reached from i over offset o: (hop_i + 1, o), compared as
@@ -1677,7 +1728,9 @@ static int enqueue(const Prepared& Q, const chert_trace_job* jobs, int n_jobs,
   int rc = phase(0);
   if (rc) return rc;
   if (outs & (CHERT_OUT_PRED_P | CHERT_OUT_PRED_A)) {
-    CHERT_LAUNCH("k_tight_out", k_tight_out, pgrid, dim3(256), 0, s, a);
+    CHERT_LAUNCH("k_tight_out", k_tight_out, dim3((unsigned)P.n_tiles),
+                 dim3((unsigned)tile_threads(a.tx, a.tz)),
+                 tight_lds_bytes(P.lw, P.lh, P.w_lds_doubles, P.n_off), s, a);
     rc = phase(1);
     if (rc) return rc;
     CHERT_LAUNCH("k_pred", k_pred, pgrid, dim3(256), 0, s, a);
