@@ -1132,11 +1132,18 @@ __device__ __forceinline__ void round_tiles(const RelaxArgs& a, int round) {
     __syncthreads();  // LDS is reused by the next tile
   }
 }
-template <int G>
-__global__ void __launch_bounds__(kRelaxThreads) k_relax_tau(RelaxArgs a, int round) {
+// LEAN: at most 64 VGPRs (8 waves per SIMD; not for G = 4, which would
+// spill), so two 1024-thread tile workgroups share a compute unit.  Pays
+// when rounds have far more active tiles than compute units; otherwise
+// the unconstrained build runs each visit faster.
+template <int G, int LEAN>
+__global__ void __launch_bounds__(kRelaxThreads)
+__attribute__((amdgpu_waves_per_eu(LEAN && G < 4 ? 8 : 1))) k_relax_tau(RelaxArgs a, int round) {
   round_tiles<G, 0>(a, round);
 }
-__global__ void __launch_bounds__(kRelaxThreads) k_relax_tree(RelaxArgs a, int round) {
+template <int LEAN>
+__global__ void __launch_bounds__(kRelaxThreads) __attribute__((amdgpu_waves_per_eu(LEAN ? 8 : 1)))
+k_relax_tree(RelaxArgs a, int round) {
   round_tiles<1, 1>(a, round);
 }
 
@@ -1438,9 +1445,12 @@ static int run_rounds(hipStream_t s, const RelaxArgs& a, void (*kern)(RelaxArgs,
 typedef void (*RoundKern)(RelaxArgs, int);
 typedef void (*PersistKern)(RelaxArgs, PersistArgs);
 
-static RoundKern round_kernel(int ph, int G) {
-  if (ph == 0) return G == 1 ? k_relax_tau<1> : (G == 2 ? k_relax_tau<2> : k_relax_tau<4>);
-  return k_relax_tree;  // one lane per frontier node: no push groups
+static RoundKern round_kernel(int ph, int G, bool lean) {
+  if (ph == 0) {
+    if (lean) return G == 1 ? k_relax_tau<1, 1> : (G == 2 ? k_relax_tau<2, 1> : k_relax_tau<4, 1>);
+    return G == 1 ? k_relax_tau<1, 0> : (G == 2 ? k_relax_tau<2, 0> : k_relax_tau<4, 0>);
+  }
+  return lean ? k_relax_tree<1> : k_relax_tree<0>;  // one lane per frontier node: no push groups
 }
 
 static PersistKern persist_kernel(int ph, int G) {
@@ -1482,6 +1492,7 @@ struct Prepared {
   int pgrid[2] = {0, 0};  // persistent-launch grid per phase
   int rgrid[2] = {0, 0};  // per-round launch grid per phase
   bool fixed_rounds = false;  // per-round launches without host checks (graphs)
+  bool lean = false;          // occupancy-limited kernel builds (large batches)
 };
 
 // Plan the batch and upload its tables (synchronous on s).
@@ -1625,12 +1636,20 @@ static int prepare(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
   Q->dL = dL;
   Q->dcol = dcol;
   const int G = o->push_group ? o->push_group : 2;
+  {
+    int dev = 0, cus = 0;
+    hipError_t e2 = hipGetDevice(&dev);
+    if (e2 == hipSuccess)
+      e2 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e2 != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e2));
+    Q->lean = P.n_tiles > 8 * (int64_t)cus;
+  }
   for (int ph = 0; ph < 2; ++ph) {
     if (o->launch == CHERT_LAUNCH_PERSISTENT)
       rc = persist_grid((const void*)persist_kernel(ph, G), tile_threads(P.tx, P.tz), Q->lds[ph],
                         P.n_tiles, &Q->pgrid[ph]);
     else
-      rc = persist_grid((const void*)round_kernel(ph, G), tile_threads(P.tx, P.tz), Q->lds[ph],
+      rc = persist_grid((const void*)round_kernel(ph, G, Q->lean), tile_threads(P.tx, P.tz), Q->lds[ph],
                         P.n_tiles, &Q->rgrid[ph]);
     if (rc) return rc;
     // per-round launches: one workgroup per tile while that is at most 4x
@@ -1715,14 +1734,14 @@ static int enqueue(const Prepared& Q, const chert_trace_job* jobs, int n_jobs,
     }
     if (Q.fixed_rounds) {  // every round of the budget, convergence read back by finish()
       for (int r = 0; r < P.max_rounds; ++r)
-        CHERT_LAUNCH(kname[ph], round_kernel(ph, G), dim3((unsigned)Q.rgrid[ph]),
+        CHERT_LAUNCH(kname[ph], round_kernel(ph, G, Q.lean), dim3((unsigned)Q.rgrid[ph]),
                      dim3((unsigned)tile_threads(a.tx, a.tz)), lds, s, a, r);
       CHERT_LAUNCH("k_round_count", k_round_count, dim3(1), dim3(1), 0, s, a.counter,
                    P.max_rounds, pa.result + ph);
       rounds[ph] = 0;
       return CHERT_OK;
     }
-    return run_rounds(s, a, round_kernel(ph, G), kname[ph], Q.rgrid[ph], lds, P.max_rounds,
+    return run_rounds(s, a, round_kernel(ph, G, Q.lean), kname[ph], Q.rgrid[ph], lds, P.max_rounds,
                       &rounds[ph]);
   };
   int rc = phase(0);

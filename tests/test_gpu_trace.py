@@ -364,3 +364,13 @@ def test_per_node_trace_bitwise(G, launch, bucket):
                        m.sources[0], subset=sub)
         print(f"mode {mode}: finite {int(np.isfinite(o['tauR']).sum())}", flush=True)
         assert_fields_equal(g, o, 0)
+
+
+def test_lean_builds_many_tiles_bitwise(G):
+    """A batch with more than 8 tiles per compute unit (8 x 8 tiles over a
+    200 x 96 grid, five sources, tau_R and tau_I problems: 3000 tiles) runs
+    the occupancy-limited kernel builds; fields, t* and predecessors still
+    equal the oracle's bitwise."""
+    m = W.small_layered(nx=200, nz=96, radius=3)
+    srcs = [0, 99, 200 * 50 + 100, 200 * 95 + 199, 200 * 20 + 30]
+    imported_case(G, m, (0,), tile=(8, 8), sources=srcs)
