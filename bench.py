@@ -107,6 +107,8 @@ def parse():
     p.add_argument("--launch", type=int, default=0,
                    help="relaxation launch: 0 tiles, one launch per round; 1 tiles, "
                         "persistent; 2 node frontier")
+    p.add_argument("--autotune", action="store_true",
+                   help="headline: let the autotuner pick tile, push group, launch and ordering")
     p.add_argument("--bucket", type=float, default=0.0,
                    help="node-frontier near/far bucket width (units of the smallest weight)")
     p.add_argument("--workload", choices=("layered", "complex2d", "shots", "3d"),
@@ -197,9 +199,23 @@ def main():
     batch = C.Batch()
     for mode in m.modes:
         batch.add(desc, cache, K, grid, mode, m.sources, **outs[mode])
+    stream = torch.cuda.current_stream()
+    tune = None
+    if args.autotune:  # pick the launch options on this batch, outside the timed steps
+        C.chert_build_cache(desc, classes, K, cache, cws, stream=stream)
+        aws = torch.empty(C.chert_trace_autotune_workspace_bytes(batch, opts),
+                          dtype=torch.uint8, device=dev)
+        t0 = time.perf_counter()
+        probe_ms = C.chert_trace_autotune(batch, opts, aws, stream=stream)
+        tune = {"s": time.perf_counter() - t0, "probe_ms": probe_ms,
+                "tile": [opts.tile_x, opts.tile_z], "push_group": opts.push_group,
+                "launch": LAUNCH_NAMES[opts.launch], "bucket_width": opts.bucket_width}
+        opts = C.trace_opts(C.OUT_ALL, tile_x=opts.tile_x, tile_z=opts.tile_z, stats=stats,
+                            push_group=opts.push_group, launch=opts.launch,
+                            bucket_width=opts.bucket_width)
+        del aws
     tws = torch.empty(C.chert_trace_batch_workspace_bytes(batch, opts), dtype=torch.uint8,
                       device=dev)
-    stream = torch.cuda.current_stream()
 
     ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for k in ("build", "trace")}
@@ -304,7 +320,10 @@ def main():
             "shots_per_s": len(m.modes) * S / (wall / args.steps),
             "useful_edges_per_field": E, "solves_per_step": solves_per_step,
             "trace_stats_last_step": st,
-            "raw_over_useful": {"tau": raw[0] / edges_per_step, "hop": raw[1] / edges_per_step},
+            "raw_over_useful": {"tau": raw[0] / edges_per_step, "tree": raw[1] / edges_per_step},
+            "launch": {"tile": [opts.tile_x or 32, opts.tile_z or 32],
+                       "push_group": opts.push_group or 2, "launch": LAUNCH_NAMES[opts.launch],
+                       "bucket_width": opts.bucket_width, "autotune": tune},
             "kernels": kernels,
         },
         "roofline": roof,
