@@ -360,8 +360,9 @@ int chert_trace_autotune(const chert_trace_job *jobs, int32_t n_jobs,
 /* The whole of a chert_trace_batch call as one replayable HIP graph:
  * create plans the batch, uploads its tables into workspace_dev
  * (synchronously on `stream`, which must not be NULL) and captures every
- * kernel -- edge weights, field initialisation, the three relaxation
- * phases, predecessors and t* -- from stream capture of `stream`.  The
+ * kernel -- edge weights, field initialisation, the traveltime phase,
+ * the tight-edge masks and the tree phase (predecessors and t*) -- from
+ * stream capture of `stream`.  The
  * phases are either the persistent launches (CHERT_LAUNCH_PERSISTENT) or,
  * with CHERT_LAUNCH_PER_ROUND and a round budget max_rounds > 0, exactly
  * max_rounds per-round launches each (rounds after convergence find no
