@@ -39,10 +39,11 @@ FP64_VALU_PEAK_TOPS = 39.3  # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz, one o
 # Valid only for the kernel source it was measured on.
 MEASURED_TRAFFIC = {
     "source": "paper_2609_26108_amd/csrc/trace.hip",
-    "source_sha256_16": "506caa21f66c0bc5",
+    "source_sha256_16": "1e3bd6232eae2041",
     "fetch_scale": 2.0, "write_scale": 1.0,
     "kib_per_dispatch": {  # kernel -> (FETCH_SIZE KiB, WRITE_SIZE KiB)
-        "k_relax_tau": (2450.5, 731.5),
+        "k_relax_tau": (2460.2, 731.6),
+        "k_relax_tree": (5180.0, 508.1),
     },
 }
 
