@@ -59,9 +59,10 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a) {
     if (!class_invalid(c) && !is_fluid_shear(c, mode)) {
       Medium m = load_medium(c);
       double thR = (j + 0.5) * (kTwoPi / a.n_sweep);
-      double thI;
-      if (theta_imag(m, mode, a.kernel, thR, &thI)) {
-        double psi = ray_angle(energy_velocity(m, mode, a.kernel, thR, thI));
+      double thI, sr, cr;
+      sincos(thR, &sr, &cr);
+      if (theta_imag_sc(m, mode, a.kernel, sr, cr, &thI)) {
+        double psi = ray_angle_sc(m, mode, a.kernel, sr, cr, thI);
         if (isfinite(psi)) out = make_double2(thI, psi);
       }
     }
@@ -133,24 +134,25 @@ __device__ __forceinline__ bool newton_root(const Medium& m, int mode, int kerne
                                          double ya, double yb, double fa, double fb,
                                          double* xo, double* yo) {
   const bool el = theta_i_zero(m, mode);
-  const double eps = 1e-7;
+  const double eps = kFdEps;
   const double dth = tb - ta;
   double t = fa / (fa - fb);
   double x = ta + t * dth;
   double y = el ? 0.0 : ya + t * (yb - ya);
   double last = 1.0;
   for (int it = 0; it < 12; ++it) {
-    Vel v0 = energy_velocity(m, mode, kernel, x, y);
+    const Trig t0 = trig_of(x, y);
+    Vel v0 = energy_velocity_t(m, mode, kernel, t0);
     double F2 = wrap_pi(ray_angle(v0) - psi_star);
     double dx, dy = 0.0;
     if (el) {
-      Vel vx = energy_velocity(m, mode, kernel, x + eps, 0.0);
+      Vel vx = energy_velocity_t(m, mode, kernel, step_re(t0));
       double d = (wrap_pi(ray_angle(vx) - psi_star) - F2) / eps;
       dx = -F2 / d;
     } else {
       double F1 = homog_residual(v0);
-      Vel vx = energy_velocity(m, mode, kernel, x + eps, y);
-      Vel vy = energy_velocity(m, mode, kernel, x, y + eps);
+      Vel vx = energy_velocity_t(m, mode, kernel, step_re(t0));
+      Vel vy = energy_velocity_t(m, mode, kernel, step_im(t0));
       double J11 = (homog_residual(vx) - F1) / eps;
       double J12 = (homog_residual(vy) - F1) / eps;
       double J21 = (wrap_pi(ray_angle(vx) - psi_star) - F2) / eps;
@@ -181,9 +183,10 @@ __device__ __forceinline__ bool bisect_root(const Medium& m, int mode, int kerne
   bool neg_lo = fa < 0.0;
   for (int it = 0; it < 200 && hi - lo > 1e-14; ++it) {
     double mid = 0.5 * (lo + hi);
-    double thI;
-    if (!theta_imag(m, mode, kernel, mid, &thI)) return false;
-    double fm = wrap_pi(ray_angle(energy_velocity(m, mode, kernel, mid, thI)) - psi_star);
+    double thI, sr, cr;
+    sincos(mid, &sr, &cr);
+    if (!theta_imag_sc(m, mode, kernel, sr, cr, &thI)) return false;
+    double fm = wrap_pi(ray_angle_sc(m, mode, kernel, sr, cr, thI) - psi_star);
     if ((fm < 0.0) == neg_lo) lo = mid;
     else hi = mid;
   }
@@ -545,10 +548,11 @@ __global__ void __launch_bounds__(kNodeThreads) k_build_fused(SolveArgs a, const
     __syncthreads();  // the previous job's solves are done with tab
     for (int j = threadIdx.x; j < a.n_sweep; j += blockDim.x) {
       const double thR = (j + 0.5) * (kTwoPi / a.n_sweep);
-      double thI;
+      double thI, sr, cr;
+      sincos(thR, &sr, &cr);
       double2 out = make_double2(0.0, NAN);
-      if (theta_imag(m, mode, a.kernel, thR, &thI)) {
-        const double psi = ray_angle(energy_velocity(m, mode, a.kernel, thR, thI));
+      if (theta_imag_sc(m, mode, a.kernel, sr, cr, &thI)) {
+        const double psi = ray_angle_sc(m, mode, a.kernel, sr, cr, thI);
         if (isfinite(psi)) out = make_double2(thI, psi);
       }
       tab[j] = out;
@@ -636,21 +640,22 @@ __global__ void __launch_bounds__(mlp::kThreads) k_warm_predict(WarmArgs w, int6
 __device__ __forceinline__ bool warm_newton(const Medium& m, int mode, int kernel, bool el,
                                          double psi_star, double x0, double y0, double* xo,
                                          double* yo, double* slope) {
-  const double eps = 1e-7;
+  const double eps = kFdEps;
   double x = x0, y = el ? 0.0 : y0, last = 1.0, sl = NAN;
   for (int it = 0; it < 16; ++it) {
-    Vel v0 = energy_velocity(m, mode, kernel, x, y);
+    const Trig t0 = trig_of(x, y);
+    Vel v0 = energy_velocity_t(m, mode, kernel, t0);
     double F2 = wrap_pi(ray_angle(v0) - psi_star);
     double dx, dy = 0.0;
     if (el) {
-      Vel vx = energy_velocity(m, mode, kernel, x + eps, 0.0);
+      Vel vx = energy_velocity_t(m, mode, kernel, step_re(t0));
       double dd = (wrap_pi(ray_angle(vx) - psi_star) - F2) / eps;
       dx = -F2 / dd;
       sl = dd;
     } else {
       double F1 = homog_residual(v0);
-      Vel vx = energy_velocity(m, mode, kernel, x + eps, y);
-      Vel vy = energy_velocity(m, mode, kernel, x, y + eps);
+      Vel vx = energy_velocity_t(m, mode, kernel, step_re(t0));
+      Vel vy = energy_velocity_t(m, mode, kernel, step_im(t0));
       double J11 = (homog_residual(vx) - F1) / eps;
       double J12 = (homog_residual(vy) - F1) / eps;
       double J21 = (wrap_pi(ray_angle(vx) - psi_star) - F2) / eps;
@@ -681,13 +686,14 @@ __device__ __forceinline__ bool thi_is_nearest(const Medium& m, int mode, int ke
                                                double y) {
   const int kr = (int)floor(fabs(y) / kThiStep);
   if (kr >= kThiSteps || y == 0.0) return false;
-  const double h0 = h_at(m, mode, kernel, x, 0.0);
+  double sr, cr;
+  sincos(x, &sr, &cr);
+  const double h0 = h_t(m, mode, kernel, sr, cr, 0.0, 1.0);
   if (h0 == 0.0) return false;
   double hp_lo = h0, hn_hi = h0;
   for (int k = 0; k <= kr; ++k) {
-    const double b = (k + 1) * kThiStep;
-    const double hp_hi = h_at(m, mode, kernel, x, b);
-    const double hn_lo = h_at(m, mode, kernel, x, -b);
+    double hp_hi, hn_lo;  // the same evaluations as theta_imag's scan
+    h_scan_pair(m, mode, kernel, sr, cr, k, &hp_hi, &hn_lo);
     const bool bp = brackets(hp_lo, hp_hi);
     const bool bn = brackets(hn_lo, hn_hi);
     if (k < kr) {
@@ -978,12 +984,13 @@ __global__ void __launch_bounds__(64) k_warm_window(WarmArgs w) {
     for (int t = lane; t < nl; t += 64) {
       const int i = s_idx[t];
       const double thR = (i + 0.5) * (kTwoPi / a.n_sweep);
-      double thI;
+      double thI, sr, cr;
+      sincos(thR, &sr, &cr);
       double2 out = make_double2(0.0, NAN);
-      if (theta_imag(m, mode, a.kernel, thR, &thI)) {
-        const double psi = ray_angle(energy_velocity(m, mode, a.kernel, thR, thI));
+      if (theta_imag_sc(m, mode, a.kernel, sr, cr, &thI)) {
+        const double psi = ray_angle_sc(m, mode, a.kernel, sr, cr, thI);
         if (isfinite(psi)) out = make_double2(thI, psi);
-        const double pe = ray_angle(energy_velocity(me, mode, a.kernel, thR, 0.0));
+        const double pe = ray_angle(energy_velocity_t(me, mode, a.kernel, Trig{sr, cr, 0.0, 1.0}));
         if (!(fabs(wrap_pi(psi - pe)) <= 0.5 * kFoldMargin)) s_bad = 1;
       }
       s_ent[t] = out;

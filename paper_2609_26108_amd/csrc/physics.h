@@ -116,12 +116,35 @@ struct Vel {
   cd v1, v3;
 };
 
-__device__ __forceinline__ Vel energy_velocity(const Medium& m, int mode, int kernel,
-                                               double thR, double thI) {
-  double sr, cr;
-  sincos(thR, &sr, &cr);
-  double sh, ch;
-  sinh_cosh(thI, &sh, &ch);
+// sin, cos of theta_R and sinh, cosh of theta_I: the only transcendental
+// inputs of the evaluation, so loops that hold theta_R (the theta_I scan)
+// or step it by a fixed amount (difference quotients) compute them once
+struct Trig {
+  double sr, cr, sh, ch;
+};
+
+__device__ __forceinline__ Trig trig_of(double thR, double thI) {
+  Trig t;
+  sincos(thR, &t.sr, &t.cr);
+  sinh_cosh(thI, &t.sh, &t.ch);
+  return t;
+}
+
+// difference-quotient step kFdEps in theta_R or theta_I by the addition
+// formulas (sine, cosine, sinh, cosh of the double nearest 1e-7)
+constexpr double kFdEps = 1e-7;
+constexpr double kSinEps = 9.999999999999982e-08, kCosEps = 0.999999999999995;
+constexpr double kSinhEps = 1.0000000000000015e-07, kCoshEps = 1.000000000000005;
+__device__ __forceinline__ Trig step_re(const Trig& t) {
+  return Trig{t.sr * kCosEps + t.cr * kSinEps, t.cr * kCosEps - t.sr * kSinEps, t.sh, t.ch};
+}
+__device__ __forceinline__ Trig step_im(const Trig& t) {
+  return Trig{t.sr, t.cr, t.sh * kCoshEps + t.ch * kSinhEps, t.ch * kCoshEps + t.sh * kSinhEps};
+}
+
+__device__ __forceinline__ Vel energy_velocity_t(const Medium& m, int mode, int kernel,
+                                                 const Trig& t) {
+  const double sr = t.sr, cr = t.cr, sh = t.sh, ch = t.ch;
   cd n1 = cd{sr * ch, cr * sh};   // sin(z)
   cd n3 = cd{cr * ch, -sr * sh};  // cos(z)
   cd n11 = n1 * n1, n33 = n3 * n3;
@@ -170,6 +193,11 @@ __device__ __forceinline__ Vel energy_velocity(const Medium& m, int mode, int ke
   return out;
 }
 
+__device__ __forceinline__ Vel energy_velocity(const Medium& m, int mode, int kernel,
+                                               double thR, double thI) {
+  return energy_velocity_t(m, mode, kernel, trig_of(thR, thI));
+}
+
 // sine of the angle between v^R and v^I (eq 9): zero when collinear
 __device__ __forceinline__ double homog_residual(const Vel& v) {
   double r1 = v.v1.re, r3 = v.v3.re, i1 = v.v1.im, i3 = v.v3.im;
@@ -190,20 +218,40 @@ __device__ __forceinline__ double h_at(const Medium& m, int mode, int kernel, do
   return homog_residual(energy_velocity(m, mode, kernel, thR, thI));
 }
 
+// residual at theta_R with sine/cosine (sr, cr) and theta_I with (sh, ch)
+__device__ __forceinline__ double h_t(const Medium& m, int mode, int kernel, double sr, double cr,
+                                      double sh, double ch) {
+  return homog_residual(energy_velocity_t(m, mode, kernel, Trig{sr, cr, sh, ch}));
+}
+
+// the outward scan's residuals at +-(k + 1) kThiStep (sinh is odd, cosh
+// even: one sinh_cosh for both sides)
+__device__ __forceinline__ void h_scan_pair(const Medium& m, int mode, int kernel, double sr,
+                                            double cr, int k, double* hp, double* hn) {
+  double sb, cb;
+  sinh_cosh((k + 1) * kThiStep, &sb, &cb);
+  *hp = h_t(m, mode, kernel, sr, cr, sb, cb);
+  *hn = h_t(m, mode, kernel, sr, cr, -sb, cb);
+}
+
 __device__ __forceinline__ bool brackets(double fa, double fb) {
   if (isnan(fa) || isnan(fb)) return false;
   return (fa < 0.0) != (fb < 0.0);
 }
 
-// Illinois (modified regula falsi) on a bracket [a, b] of h(thR, .)
-__device__ __forceinline__ double refine_thi(const Medium& m, int mode, int kernel, double thR,
-                                             double a, double b, double fa, double fb) {
+// Illinois (modified regula falsi) on a bracket [a, b] of h(thR, .);
+// (sr, cr) = sine and cosine of thR
+__device__ __forceinline__ double refine_thi(const Medium& m, int mode, int kernel, double sr,
+                                             double cr, double a, double b, double fa,
+                                             double fb) {
   int side = 0;
   double c = 0.5 * (a + b);
   for (int it = 0; it < 80; ++it) {
     double cn = (a * fb - b * fa) / (fb - fa);
     if (!(cn > fmin(a, b) && cn < fmax(a, b))) cn = 0.5 * (a + b);
-    double fc = h_at(m, mode, kernel, thR, cn);
+    double shc, chc;
+    sinh_cosh(cn, &shc, &chc);
+    double fc = h_t(m, mode, kernel, sr, cr, shc, chc);
     double step = fabs(cn - c);
     c = cn;
     if (fc == 0.0) break;
@@ -226,14 +274,15 @@ __device__ __forceinline__ double refine_thi(const Medium& m, int mode, int kern
 // theta_I(theta_R): root of the homogeneity residual nearest 0 in [-30, 30]
 // deg, found by an outward 0.25-degree scan.  Returns false if none.
 // Written for wavefront lockstep: every lane first scans until the whole
-// wavefront has its bracket, then all lanes refine together.
-__device__ __forceinline__ bool theta_imag(const Medium& m, int mode, int kernel, double thR,
-                                           double* thI) {
+// wavefront has its bracket, then all lanes refine together.  (sr, cr) =
+// sine and cosine of thR.
+__device__ __forceinline__ bool theta_imag_sc(const Medium& m, int mode, int kernel, double sr,
+                                              double cr, double* thI) {
   if (theta_i_zero(m, mode)) {
     *thI = 0.0;
     return true;
   }
-  double h0 = h_at(m, mode, kernel, thR, 0.0);
+  double h0 = h_t(m, mode, kernel, sr, cr, 0.0, 1.0);
   bool done = (h0 == 0.0);
   bool bp = false, bn = false;
   double pa = 0.0, pb = 0.0, fpa = 0.0, fpb = 0.0;  // positive-side bracket
@@ -242,8 +291,8 @@ __device__ __forceinline__ bool theta_imag(const Medium& m, int mode, int kernel
   for (int k = 0; k < kThiSteps; ++k) {
     if (!done) {
       double a = k * kThiStep, b = (k + 1) * kThiStep;
-      double hp_hi = h_at(m, mode, kernel, thR, b);
-      double hn_lo = h_at(m, mode, kernel, thR, -b);
+      double hp_hi, hn_lo;
+      h_scan_pair(m, mode, kernel, sr, cr, k, &hp_hi, &hn_lo);
       bp = brackets(hp_lo, hp_hi);
       bn = brackets(hn_lo, hn_hi);
       if (bp) { pa = a; pb = b; fpa = hp_lo; fpb = hp_hi; }
@@ -259,11 +308,26 @@ __device__ __forceinline__ bool theta_imag(const Medium& m, int mode, int kernel
     return true;
   }
   if (!bp && !bn) return false;
-  double rp = bp ? refine_thi(m, mode, kernel, thR, pa, pb, fpa, fpb) : 0.0;
-  double rn = bn ? refine_thi(m, mode, kernel, thR, na, nb, fna, fnb) : 0.0;
+  double rp = bp ? refine_thi(m, mode, kernel, sr, cr, pa, pb, fpa, fpb) : 0.0;
+  double rn = bn ? refine_thi(m, mode, kernel, sr, cr, na, nb, fna, fnb) : 0.0;
   if (bp && bn) *thI = (fabs(rn) < fabs(rp)) ? rn : rp;
   else *thI = bp ? rp : rn;
   return true;
+}
+
+__device__ __forceinline__ bool theta_imag(const Medium& m, int mode, int kernel, double thR,
+                                           double* thI) {
+  double sr, cr;
+  sincos(thR, &sr, &cr);
+  return theta_imag_sc(m, mode, kernel, sr, cr, thI);
+}
+
+// ray angle at (thR, thI) given sin, cos of thR
+__device__ __forceinline__ double ray_angle_sc(const Medium& m, int mode, int kernel, double sr,
+                                               double cr, double thI) {
+  double sh, ch;
+  sinh_cosh(thI, &sh, &ch);
+  return ray_angle(energy_velocity_t(m, mode, kernel, Trig{sr, cr, sh, ch}));
 }
 
 struct Entry {
