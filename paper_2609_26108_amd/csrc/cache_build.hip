@@ -147,7 +147,7 @@ __device__ __forceinline__ bool newton_root(const Medium& m, int mode, int kerne
     double dx, dy = 0.0;
     if (el) {
       Vel vx = energy_velocity_t(m, mode, kernel, step_re(t0));
-      double d = (wrap_pi(ray_angle(vx) - psi_star) - F2) / eps;
+      double d = dangle(v0, vx) / eps;
       dx = -F2 / d;
     } else {
       double F1 = homog_residual(v0);
@@ -155,8 +155,8 @@ __device__ __forceinline__ bool newton_root(const Medium& m, int mode, int kerne
       Vel vy = energy_velocity_t(m, mode, kernel, step_im(t0));
       double J11 = (homog_residual(vx) - F1) / eps;
       double J12 = (homog_residual(vy) - F1) / eps;
-      double J21 = (wrap_pi(ray_angle(vx) - psi_star) - F2) / eps;
-      double J22 = (wrap_pi(ray_angle(vy) - psi_star) - F2) / eps;
+      double J21 = dangle(v0, vx) / eps;
+      double J22 = dangle(v0, vy) / eps;
       double det = J11 * J22 - J12 * J21;
       dx = -(J22 * F1 - J12 * F2) / det;
       dy = -(-J21 * F1 + J11 * F2) / det;
@@ -649,7 +649,7 @@ __device__ __forceinline__ bool warm_newton(const Medium& m, int mode, int kerne
     double dx, dy = 0.0;
     if (el) {
       Vel vx = energy_velocity_t(m, mode, kernel, step_re(t0));
-      double dd = (wrap_pi(ray_angle(vx) - psi_star) - F2) / eps;
+      double dd = dangle(v0, vx) / eps;
       dx = -F2 / dd;
       sl = dd;
     } else {
@@ -658,8 +658,8 @@ __device__ __forceinline__ bool warm_newton(const Medium& m, int mode, int kerne
       Vel vy = energy_velocity_t(m, mode, kernel, step_im(t0));
       double J11 = (homog_residual(vx) - F1) / eps;
       double J12 = (homog_residual(vy) - F1) / eps;
-      double J21 = (wrap_pi(ray_angle(vx) - psi_star) - F2) / eps;
-      double J22 = (wrap_pi(ray_angle(vy) - psi_star) - F2) / eps;
+      double J21 = dangle(v0, vx) / eps;
+      double J22 = dangle(v0, vy) / eps;
       double det = J11 * J22 - J12 * J21;
       dx = -(J22 * F1 - J12 * F2) / det;
       dy = -(-J21 * F1 + J11 * F2) / det;

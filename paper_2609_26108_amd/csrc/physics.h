@@ -206,6 +206,12 @@ __device__ __forceinline__ double homog_residual(const Vel& v) {
 
 __device__ __forceinline__ double ray_angle(const Vel& v) { return atan2(v.v1.re, v.v3.re); }
 
+// angle of w minus angle of v for nearly parallel v, w (difference
+// quotients): the tangent of the difference, exact to third order
+__device__ __forceinline__ double dangle(const Vel& v, const Vel& w) {
+  return (v.v3.re * w.v1.re - v.v1.re * w.v3.re) / (v.v1.re * w.v1.re + v.v3.re * w.v3.re);
+}
+
 // into (-pi, pi]
 __device__ __forceinline__ double wrap_pi(double a) {
   if (a > kPi) a -= kTwoPi;
