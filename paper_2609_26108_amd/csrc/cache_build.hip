@@ -750,8 +750,11 @@ __device__ __forceinline__ void mark_window(const SolveArgs& a, const double* ps
 __device__ __forceinline__ void proxy_folds(const Medium& me, int mode, int kernel, double* s_psi,
                                             uint32_t* s_fold, int* s_all) {
   const int lane = threadIdx.x;
-  for (int j = lane; j < kProxyN; j += 64)
-    s_psi[j] = ray_angle(energy_velocity(me, mode, kernel, (j + 0.5) * (kPi / kProxyN), 0.0));
+  for (int j = lane; j < kProxyN; j += 64) {
+    double sr, cr;  // real angle: sinh 0 = 0, cosh 0 = 1
+    sincos((j + 0.5) * (kPi / kProxyN), &sr, &cr);
+    s_psi[j] = ray_angle(energy_velocity_t(me, mode, kernel, Trig{sr, cr, 0.0, 1.0}));
+  }
   __syncthreads();
   for (int j = lane; j < kProxyN; j += 64) {
     const double pa = s_psi[j];

@@ -175,21 +175,23 @@ __device__ __forceinline__ Vel energy_velocity_t(const Medium& m, int mode, int 
   cd c = csqrt_p(G);
   cd p1, p3;
   cdiv2(n1, n3, c, &p1, &p3);
-  cd S11, S33, S13;
   if (kernel == CHERT_KERNEL_OEV) {
     cd N = g1 * g1 + g3 * g3;
-    S11 = cdiv(g1 * g1, N);
-    S33 = cdiv(g3 * g3, N);
-    S13 = cdiv(g1 * g3, N);
-  } else {
-    double q1 = norm2(g1), q3 = norm2(g3);
-    const double invN = 1.0 / (q1 + q3);
-    S11 = cd{q1 * invN, 0.0};
-    S33 = cd{q3 * invN, 0.0};
-    S13 = cd{(g1.re * g3.re + g1.im * g3.im) * invN, 0.0};
+    cd S11 = cdiv(g1 * g1, N);
+    cd S33 = cdiv(g3 * g3, N);
+    cd S13 = cdiv(g1 * g3, N);
+    out.v1 = p1 * (m.a11 * S11 + m.a44 * S33) + p3 * (a1344 * S13);
+    out.v3 = p3 * (m.a33 * S33 + m.a44 * S11) + p1 * (a1344 * S13);
+    return out;
   }
-  out.v1 = p1 * (m.a11 * S11 + m.a44 * S33) + p3 * (a1344 * S13);
-  out.v3 = p3 * (m.a33 * S33 + m.a44 * S11) + p1 * (a1344 * S13);
+  // MEV: S = Re(g g^H) / (g^H g) is real, so moduli scale by reals
+  double q1 = norm2(g1), q3 = norm2(g3);
+  const double invN = 1.0 / (q1 + q3);
+  const double S11 = q1 * invN, S33 = q3 * invN;
+  const double S13 = (g1.re * g3.re + g1.im * g3.im) * invN;
+  const cd B = S13 * a1344;
+  out.v1 = p1 * (S11 * m.a11 + S33 * m.a44) + p3 * B;
+  out.v3 = p3 * (S33 * m.a33 + S11 * m.a44) + p1 * B;
   return out;
 }
 
