@@ -42,8 +42,8 @@ MEASURED_TRAFFIC = {
     "source_sha256_16": "1e3bd6232eae2041",
     "fetch_scale": 2.0, "write_scale": 1.0,
     "kib_per_dispatch": {  # kernel -> (FETCH_SIZE KiB, WRITE_SIZE KiB)
-        "k_relax_tau": (2460.2, 731.6),
-        "k_relax_tree": (5180.0, 508.1),
+        "k_relax_tau": (2462.3, 733.7),
+        "k_relax_tree": (5203.9, 507.7),
     },
 }
 
@@ -70,9 +70,9 @@ def measured_traffic_bytes(kernel):
 MEASURED_FP64 = {
     "sources": ["paper_2609_26108_amd/csrc/cache_build.hip",
                 "paper_2609_26108_amd/csrc/physics.h", "paper_2609_26108_amd/csrc/mlp.h"],
-    "sources_sha256_16": "89e2c5c1888fe73e",
-    "flops_per_dispatch": {"k_warm_solve": 7.4710e11, "k_warm_window": 3.8901e11,
-                           "k_warm_fold": 2.1129e10, "k_warm_predict": 5.3496e9},
+    "sources_sha256_16": "9e3ec4b953efb8ed",
+    "flops_per_dispatch": {"k_warm_solve": 4.9490e11, "k_warm_window": 2.8717e11,
+                           "k_warm_fold": 1.3738e10, "k_warm_predict": 5.3496e9},
 }
 
 
