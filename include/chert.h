@@ -238,7 +238,8 @@ typedef struct chert_trace_stats {
 /* How the relaxation rounds are launched (the fields are the same either
  * way: the fixed point does not depend on the schedule):
  *   PER_ROUND   one launch per round over every tile; the host checks for
- *               termination every 8 rounds;
+ *               termination after 16, then every 32, then every 64 rounds
+ *               (launches past convergence find no active tile);
  *   PERSISTENT  one launch per phase: an occupancy-sized grid walks each
  *               round's active tiles, rounds separated by a device-wide
  *               barrier (bounded wait: a stalled barrier fails the call with

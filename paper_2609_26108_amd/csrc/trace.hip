@@ -1418,11 +1418,15 @@ static int make_plan(const chert_trace_job* jobs, int n_jobs, const chert_trace_
   return CHERT_OK;
 }
 
+// Rounds go out in groups between host checks of the round counters:
+// 16, then 32, then 64 at a time (a converged phase's extra launches find
+// no active tile and leave at once; each check costs a stream drain).
 static int run_rounds(hipStream_t s, const RelaxArgs& a, void (*kern)(RelaxArgs, int),
                       const char* name, int grid, size_t lds, int max_rounds, int* rounds) {
-  const int batch = 8;
-  int32_t counts[batch];
-  for (int r = 0; r < max_rounds; r += batch) {
+  constexpr int kMaxBatch = 64;
+  int32_t counts[kMaxBatch];
+  int batch = 16;
+  for (int r = 0; r < max_rounds; r += batch, batch = std::min(2 * batch, kMaxBatch)) {
     int nb = batch;
     if (r + nb > max_rounds) nb = max_rounds - r;
     for (int q = 0; q < nb; ++q)
