@@ -924,7 +924,6 @@ __global__ void __launch_bounds__(64) k_warm_window(WarmArgs w) {
     const int64_t k = job % a.n_classes;
     const int mode = a.modes[job / a.n_classes];
     const chert_class c = a.classes[k];
-    const int64_t row = ((int64_t)mode * a.n_classes + k) * a.n_cols;
     const Medium m = load_medium(c);
     const Medium me = elastic_of(m);
     __syncthreads();  // the previous job is done with the shared arrays
