@@ -692,6 +692,23 @@ def run_shots(args):
     shots = 2 * sum(len(m.sources) for m in models)
     res["eager"] = {"s": t_eager, "shots_per_s": shots / t_eager,
                     "star_edges_per_s_tau_fields": E_total / t_eager, "stats": stats.as_dict()}
+    # HBM roofline of the traveltime kernel on per-node caches, from one more
+    # eager run with HIP events around its launches: algorithmic bytes = per
+    # (problem, node) its weight row (|O| doubles) plus tau read and written
+    C.chert_prof_enable(True, only="k_relax_tau")
+    C.chert_trace_batch(b, opts_s, ws, stream=stream)
+    torch.cuda.synchronize()
+    prof = C.chert_prof_read()
+    C.chert_prof_enable(False)
+    if "k_relax_tau" in prof:
+        n_launch, ms_tau = prof["k_relax_tau"]
+        n_off = len(ox)
+        alg = sum(2 * len(m.sources) * m.n_nodes * (n_off * 8 + 16) for m in models)
+        gbs = alg / (ms_tau * 1e-3) / 1e9
+        res["roofline"] = {"kernel": "k_relax_tau", "bound": "hbm", "achieved": gbs,
+                           "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0, "traffic": None,
+                           "work": f"{alg / 1e9:.1f} GB algorithmic over {int(n_launch)} launches",
+                           "phase_ms": ms_tau}
     for bw in args.shots_buckets:
         st_b = C.TraceStats()
         ob = C.trace_opts(outs, opts.tile_x, opts.tile_z, push_group=opts.push_group,
