@@ -374,3 +374,41 @@ def test_lean_builds_many_tiles_bitwise(G):
     m = W.small_layered(nx=200, nz=96, radius=3)
     srcs = [0, 99, 200 * 50 + 100, 200 * 95 + 199, 200 * 20 + 30]
     imported_case(G, m, (0,), tile=(8, 8), sources=srcs)
+
+
+def test_lean_builds_per_node_many_sources_bitwise(G):
+    """Per-node cache, 35 sources on one grid with 8 x 8 tiles (2 x 35 x 30 =
+    2100 tiles: the occupancy-limited builds on the per-node weight path);
+    every source's fields and predecessors equal the oracle's bitwise."""
+    import torch
+    Cm = C()
+    m = W.complex_2d(nx=45, nz=33, h=10.0, water_m=60.0, n_layers=8, n_faults=2, seed=5,
+                     radius=3, modes=(0, 1))
+    rows = m.param_rows()
+    cls = np.stack([O.class_from_thomsen(*r) for r in rows])
+    sub = O.star_subset(3, m.hx, m.hz)
+    f, s = O.build_cache_2d(cls, mode_mask=0b001, n_sweep=360, subset=sub)
+    desc = Cm.cache_desc(modes=(0,), n_sweep=360, subset=sub)
+    N = rows.shape[0]
+    cache = G.import_cache(f, s, desc, N)
+    n = m.n_nodes
+    srcs = [int(v) for v in np.linspace(0, n - 1, 35).astype(np.int64)]
+    S = len(srcs)
+    out = dict(tau_r=torch.empty((S, n), dtype=torch.float64, device=G.DEV),
+               tau_i=torch.empty((S, n), dtype=torch.float64, device=G.DEV),
+               tstar=torch.empty((S, n), dtype=torch.float64, device=G.DEV),
+               pred_p=torch.empty((S, n), dtype=torch.int32, device=G.DEV),
+               pred_a=torch.empty((S, n), dtype=torch.int32, device=G.DEV))
+    grid = Cm.make_grid(m.nx, m.nz, m.hx, m.hz, m.radius, None)
+    opts = Cm.trace_opts(Cm.OUT_ALL, tile_x=8, tile_z=8)
+    ws = torch.empty(Cm.chert_trace_workspace_bytes(desc, N, grid, S, opts), dtype=torch.uint8,
+                     device=G.DEV)
+    Cm.chert_trace_field(desc, cache, N, grid, 0, srcs, opts, workspace_dev=ws, **out)
+    torch.cuda.synchronize()
+    g = {"tauR": out["tau_r"].cpu().numpy(), "tauI": out["tau_i"].cpu().numpy(),
+         "tstar": out["tstar"].cpu().numpy(), "predP": out["pred_p"].cpu().numpy(),
+         "predA": out["pred_a"].cpu().numpy()}
+    for si, src in enumerate(srcs):
+        o = O.trace_2d(m.nx, m.nz, m.hx, m.hz, None, m.radius, f[0, 0], f[1, 0], s[0], src,
+                       subset=sub)
+        assert_fields_equal(g, o, si)
