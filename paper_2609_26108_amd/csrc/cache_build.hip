@@ -9,7 +9,13 @@
 //            iteration on (homogeneity residual, ray-direction miss), keeps
 //            the largest ray velocity (first arrival) and writes the entry and
 //            its centrosymmetric copy (eqs 10-11).
-// Everything is FP64: qSV cusps and triplications need it.
+// Per-node caches (one class per node) run both steps per job in one
+// workgroup (k_build_fused), or start from the surrogate's prediction:
+// k_warm_predict (MLP on the matrix cores), k_warm_solve (Newton polish
+// and the checks that the plain search would return the same root),
+// k_warm_window and k_warm_fold (the plain search's brackets near fold
+// directions), with k_build_fused re-solving any job that fails a check.
+// Everything is FP64 except the MLP: qSV cusps and triplications need it.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>

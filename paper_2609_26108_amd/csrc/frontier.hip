@@ -1,8 +1,10 @@
 // Node-frontier label-correcting traveltimes (eq 31 over the forward star,
-// edge costs of eqs 27-30) for gfx950.  Every 3D batch runs here, and so do
-// 2D batches that ask for CHERT_LAUNCH_FRONTIER; trace.hip holds the 2D tile
-// relaxation.  Both reach the fixed point Dijkstra reaches from the same
-// weights.
+// edge costs of eqs 27-30) for gfx950.  Every 3D batch runs here: its
+// traveltimes on this node frontier (CHERT_LAUNCH_FRONTIER) or on the 3D
+// tiles of tile3d.hip (CHERT_LAUNCH_PER_ROUND), its predecessors and t*
+// always here.  2D batches that ask for CHERT_LAUNCH_FRONTIER run here too;
+// trace.hip holds the 2D tile relaxation.  All reach the fixed point
+// Dijkstra reaches from the same weights.
 //
 // Iteration it relaxes every out-edge of the (problem, node) items whose
 // traveltime dropped in iteration it - 1, one thread per (item, offset): an
@@ -17,8 +19,8 @@
 // entered once (the hop atomicMin is its own dedupe), all layers stored in
 // order in one list.  pred_j is the tight in-neighbour at hop_j - 1 with the
 // smallest offset index, and t* folds the attenuation weights along the
-// propagation predecessors layer by layer: the rule and the fold of the tile
-// path.
+// propagation predecessors layer by layer: the rule and the fold of the 2D
+// tile path's tree phase.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>

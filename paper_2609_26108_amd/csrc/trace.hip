@@ -7,11 +7,13 @@
 // 29-31).  All problems advance together in the same launches:
 //   - every grid is cut into TX x TZ tiles; a workgroup owns one (problem,
 //     tile) per round, stages the tile plus an R-wide halo of the field and
-//     the class ids in LDS, pulls every interior node once over the star,
-//     then runs push iterations over a compacted frontier of improved nodes
+//     the class ids in LDS, pulls the interior nodes within R of the halo
+//     parts that changed (all of them on a full visit) over the star, then
+//     runs push iterations over a compacted frontier of improved nodes
 //     (LDS 64-bit atomic min) until the tile is locally converged;
 //   - changed nodes within R of a tile border activate the neighbouring
-//     tile for the next round (double-buffered flags, one counter per round);
+//     tile for the next round with the side they changed (double-buffered
+//     flags, one counter per round);
 //   - rounds repeat until a round activates nothing.
 // Every value ever written is the left-to-right FP64 sum along some path and
 // values only decrease, so the fixed point is the minimum over paths --
