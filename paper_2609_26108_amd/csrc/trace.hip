@@ -1017,22 +1017,47 @@ __device__ __forceinline__ void relax_tree(const RelaxArgs& a, int round, int T)
       const int i = live ? lcur[f] : 0;
       const unsigned long long ki = live ? s.key[i] : kKeyUnset;
       const bool has = ki != kKeyUnset;
-      int w = 0;
-      uint32_t m = has ? s.om[i] : 0u;
-      while (true) {
-        while (m == 0u && has && ++w < nw) m = s.om[w * n + i];
-        if (__ballot(m != 0u) == 0ull) break;
+      // the wavefront's tight out-edges dealt one per lane: a lane's count,
+      // inclusive prefix over the wavefront, then edge e goes to the lane
+      // holding it (first lane whose inclusive prefix exceeds e)
+      int cnt = 0;
+      for (int w = 0; w < nw; ++w) cnt += has ? __popc(s.om[w * n + i]) : 0;
+      const int lane = __lane_id();
+      int incl = cnt;
+      for (int d = 1; d < 64; d <<= 1) {
+        const int v = __shfl_up(incl, d);
+        if (lane >= d) incl += v;
+      }
+      const int excl = incl - cnt;
+      const int total = __shfl(incl, 63);
+      for (int e0 = 0; e0 < total; e0 += 64) {
+        const int e = e0 + lane;
+        int owner = 0;
+        for (int step = 32; step > 0; step >>= 1)
+          if (__shfl(incl, owner + step - 1) <= e) owner += step;
+        owner = owner > 63 ? 63 : owner;
+        const int ex_o = __shfl(excl, owner);
+        const int io = __shfl(i, owner);
+        const unsigned long long ko = __shfl(ki, owner);
         bool mark = false;
         int jj = 0;
-        if (m != 0u) {
-          const int b = __ffs(m) - 1;
-          m &= m - 1u;
-          const int o = w * 32 + b;
-          const int j = i + s.off[o];
+        if (e < total) {
+          int k = e - ex_o, o = -1;  // the owner's k-th set bit
+          for (int w = 0; w < nw; ++w) {
+            uint32_t m = s.om[w * n + io];
+            const int pc = __popc(m);
+            if (o < 0 && k < pc) {
+              for (int t = 0; t < k; ++t) m &= m - 1u;
+              o = w * 32 + __ffs(m) - 1;
+            } else if (o < 0) {
+              k -= pc;
+            }
+          }
+          const int j = io + s.off[o];
           const int kj = s.cls[j];
           ++raw;
           if (kj >= 0 && !(kj & kHaloBit)) {
-            const unsigned long long cand = tree_key(ki, o);
+            const unsigned long long cand = tree_key(ko, o);
             if (cand < s.key[j] || (fold && cand == s.key[j])) {
               const unsigned long long old = atomicMin(&s.key[j], cand);
               if (cand < old) {
