@@ -57,7 +57,7 @@ constexpr int kFlagSeed = 4;    // first visit of the source tile: push the sour
 // bits kSideShift + s, s = (sz + 1) * 3 + (sx + 1): the halo part facing the
 // neighbour at (sx, sz) changed, so the nodes within R of that side re-pull
 constexpr int kSideShift = 3;
-constexpr int kPullChunk = 8;  // per-node pulls: weight loads issued together
+constexpr int kPullGroup = 8;  // offsets per item of a tile's distributed pull
 // LDS class ids of halo cells carry this bit (push targets must be interior)
 constexpr int32_t kHaloBit = 0x40000000;
 constexpr int32_t kClassMask = 0x3fffffff;
@@ -568,50 +568,42 @@ __device__ __forceinline__ void relax_tau(const RelaxArgs& a, int round, int T) 
   long long raw = 0;
   const double orig = ml >= 0 ? s.val[ml] : 0.0;
 
-  // pull over the border band (or every node), then seed the source
+  // Pull over the border band (or every node), then seed the source.  The
+  // pulled nodes' in-edges are spread over the block as items (node, group
+  // of kPullGroup offsets) -- not one node's whole star per thread, which
+  // kept a wavefront waiting on its few pulling lanes -- each lowering its
+  // node with the 64-bit LDS atomic min; a node whose value dropped enters
+  // the first frontier.  (In-neighbours lowered meanwhile enter it too.)
   {
-    bool improved = false;
-    if (ml >= 0 && pulls(a, c, ml)) {
-      atomicAdd(&s_npull, 1);
-      const int kj = s.cls[ml];
-      if (kj >= 0) {
-        const int64_t gml = gnode(a, c, jb, ml);
-        const double cur = s.val[ml];
-        double best = cur;
-        if (jb.per_node) {
-          // the node's weight row from HBM, kPullChunk loads in flight at a time
-          const double* wrow = jb.W + ((int64_t)pr.field * jb.nx * jb.nz + gml) * n_off;
-          for (int o0 = 0; o0 < n_off; o0 += kPullChunk) {
-            double wv[kPullChunk];
+    const bool pl = ml >= 0 && pulls(a, c, ml) && s.cls[ml] >= 0;
+    if (pl) atomicAdd(&s_npull, 1);
+    frontier_add(pl, ml, s.l1, &s_cnt[1]);  // l1 is free until the first level
+    __syncthreads();
+    const int np = s_cnt[1];
+    const int npg = (n_off + kPullGroup - 1) / kPullGroup;
+    const int total = np * npg;
+    for (int item = threadIdx.x; item < total; item += blockDim.x) {
+      const int j = s.l1[item / npg], g = item % npg;
+      const int kj = s.cls[j];
+      const int64_t gj = gnode(a, c, jb, j);
+      double best = s.val[j];
 #pragma unroll
-            for (int u = 0; u < kPullChunk; ++u) wv[u] = o0 + u < n_off ? wrow[o0 + u] : 0.0;
-#pragma unroll
-            for (int u = 0; u < kPullChunk; ++u) {
-              const int o = o0 + u;
-              if (o >= n_off) break;
-              const int ii = ml - s.off[o];
-              if (s.cls[ii] < 0) continue;
-              const double cand = __dadd_rn(s.val[ii], wv[u]);
-              if (cand < best) best = cand;
-            }
-          }
-        } else {
-          for (int o = 0; o < n_off; ++o) {
-            const int ii = ml - s.off[o];
-            const int ki = s.cls[ii];
-            if (ki < 0) continue;
-            const double cand = __dadd_rn(
-                s.val[ii], w_pull(jb, Wp, pr.field, ki & kClassMask, kj, o, n_off, gml));
-            if (cand < best) best = cand;
-          }
-        }
-        if (best < cur) {
-          s.val[ml] = best;
-          improved = true;
-          s.inq[ml] = 1;
-        }
+      for (int u = 0; u < kPullGroup; ++u) {
+        const int o = g * kPullGroup + u;
+        if (o >= n_off) break;
+        const int ii = j - s.off[o];
+        const int ki = s.cls[ii];
+        if (ki < 0) continue;
+        const double cand =
+            __dadd_rn(s.val[ii], w_pull(jb, Wp, pr.field, ki & kClassMask, kj, o, n_off, gj));
+        if (cand < best) best = cand;
       }
+      if (best < s.val[j]) atomicMin((unsigned long long*)&s.val[j], dbits(best));
     }
+    __syncthreads();
+    if (threadIdx.x == 0) s_cnt[1] = 0;  // every thread has read np
+    const bool improved = pl && s.val[ml] < orig;
+    if (improved) s.inq[ml] = 1;
     frontier_add(improved, ml, s.l0, &s_cnt[0]);
   }
   if (threadIdx.x == 0) {
