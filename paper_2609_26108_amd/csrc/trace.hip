@@ -955,27 +955,39 @@ __device__ __forceinline__ void relax_tree(const RelaxArgs& a, int round, int T)
     return true;
   };
 
-  // pull over the border band (or every node), then seed the source
+  // pull over the border band (or every node), then seed the source: the
+  // pulled nodes' in-edges as (node, kPullGroup offsets) items over the
+  // block (64-bit LDS atomic min on the key), then each pulled node
+  // re-reads its t*
   {
-    bool changed = false;
-    if (ml >= 0 && pulls(a, c, ml)) {
-      atomicAdd(&s_npull, 1);
-      unsigned long long best = s.key[ml];
-      for (int o = 0; o < n_off; ++o) {
-        const int ii = ml - s.off[o];
+    const bool pl = ml >= 0 && pulls(a, c, ml);
+    if (pl) atomicAdd(&s_npull, 1);
+    frontier_add(pl, ml, s.l1, &s_cnt[1]);  // l1 is free until the first level
+    __syncthreads();
+    const int np = s_cnt[1];
+    const int npg = (n_off + kPullGroup - 1) / kPullGroup;
+    const int total = np * npg;
+    for (int item = threadIdx.x; item < total; item += blockDim.x) {
+      const int j = s.l1[item / npg], g = item % npg;
+      unsigned long long best = s.key[j];
+#pragma unroll
+      for (int u = 0; u < kPullGroup; ++u) {
+        const int o = g * kPullGroup + u;
+        if (o >= n_off) break;
+        const int ii = j - s.off[o];
         if (!((s.om[(o >> 5) * n + ii] >> (o & 31)) & 1u)) continue;
         const unsigned long long ki = s.key[ii];
         if (ki == kKeyUnset) continue;
         const unsigned long long cand = tree_key(ki, o);
         if (cand < best) best = cand;
       }
-      if (best < s.key[ml]) {
-        s.key[ml] = best;
-        changed = true;
-      }
-      if (fold && refold(ml)) changed = true;
-      if (changed) s.inq[ml] = 2;
+      if (best < s.key[j]) atomicMin(&s.key[j], best);
     }
+    __syncthreads();
+    if (threadIdx.x == 0) s_cnt[1] = 0;  // every thread has read np
+    bool changed = pl && s.key[ml] != okey;
+    if (pl && fold && refold(ml)) changed = true;
+    if (changed) s.inq[ml] = 2;
     frontier_add(changed, ml, s.l0, &s_cnt[0]);
   }
   if (threadIdx.x == 0) {
@@ -985,9 +997,7 @@ __device__ __forceinline__ void relax_tree(const RelaxArgs& a, int round, int T)
   }
   __syncthreads();
 
-  // push levels: each frontier node walks only its tight out-edges (one
-  // lane per node, bits taken one at a time; the loop runs while any lane
-  // of the wavefront has one left)
+  // push levels over the tight out-edges of the frontier nodes only
   int ci = 0, it = 1;
   int nf = s_cnt[0];
   const int nt = blockDim.x;
