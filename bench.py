@@ -263,6 +263,39 @@ def main():
     C.chert_prof_enable(False)
     ms = 1e3 * wall / args.steps
 
+    # the same steps with the trace replayed as one HIP graph (per-round
+    # launches, round budget from the eager runs): no host checks or table
+    # uploads inside the step.  Reported beside the eager figure.
+    graph_ms = None
+    if args.launch == C.LAUNCH_PER_ROUND:
+        budget = max(stats.rounds[0], stats.rounds[1]) + 4
+        gopts = C.trace_opts(C.OUT_ALL, tile_x=opts.tile_x, tile_z=opts.tile_z,
+                             push_group=opts.push_group, launch=C.LAUNCH_PER_ROUND,
+                             bucket_width=opts.bucket_width, max_rounds=budget)
+        gws = torch.empty(C.chert_trace_batch_workspace_bytes(batch, gopts), dtype=torch.uint8,
+                          device=dev)
+        gstream = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(gstream):
+            graph = C.TraceGraph(batch, gopts, gws, stream=gstream)
+            try:
+                gst = C.TraceStats()
+                for _ in range(2):  # warm-up replays
+                    C.chert_build_cache(desc, classes, K, cache, cws, stream=gstream)
+                    graph.launch(gstream)
+                    graph.finish(gst, gstream)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    C.chert_build_cache(desc, classes, K, cache, cws, stream=gstream)
+                    graph.launch(gstream)
+                    graph.finish(gst, gstream)  # waits, checks convergence in the budget
+                torch.cuda.synchronize()
+                graph_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+            finally:
+                graph.close()
+        del gws
+
     ox, oz, L, b = C.chert_star_2d(m.radius, m.hx, m.hz, m.n_dirs)
     E = useful_edges(m.nx, m.nz, ox, oz)
     fields_per_step = 2 * len(m.modes)
@@ -322,6 +355,7 @@ def main():
             "useful_edges_per_field": E, "solves_per_step": solves_per_step,
             "trace_stats_last_step": st,
             "raw_over_useful": {"tau": raw[0] / edges_per_step, "tree": raw[1] / edges_per_step},
+            "graph_ms_per_step": graph_ms,
             "launch": {"tile": [opts.tile_x or 32, opts.tile_z or 32],
                        "push_group": opts.push_group or 2, "launch": LAUNCH_NAMES[opts.launch],
                        "bucket_width": opts.bucket_width, "autotune": tune},
