@@ -30,6 +30,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cstring>
 #include <new>
 #include <vector>
 
@@ -1621,15 +1622,15 @@ static int prepare(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
   }
   JobDev* djobs = (JobDev*)(ws + P.off_jobs);
   ProbDev* dprobs = (ProbDev*)(ws + P.off_probs);
-  hipError_t e = hipMemcpyAsync(dox, star.data(), star.size() * sizeof(int32_t),
-                                hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(dL, lbin.data(), lbin.size(), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(djobs, jd.data(), jd.size() * sizeof(JobDev), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(dprobs, probs.data(), probs.size() * sizeof(ProbDev),
-                       hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);  // host buffers are locals
+  // the star, lengths/bins, job and problem tables lie in order at the
+  // start of the workspace: one upload for all four
+  std::vector<uint8_t> up(P.off_probs + probs.size() * sizeof(ProbDev), 0);
+  memcpy(up.data() + P.off_star, star.data(), star.size() * sizeof(int32_t));
+  memcpy(up.data() + P.off_lbin, lbin.data(), lbin.size());
+  memcpy(up.data() + P.off_jobs, jd.data(), jd.size() * sizeof(JobDev));
+  memcpy(up.data() + P.off_probs, probs.data(), probs.size() * sizeof(ProbDev));
+  hipError_t e = hipMemcpyAsync(ws, up.data(), up.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host buffer is a local
   if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
 
   RelaxArgs& a = Q->a;
