@@ -39,7 +39,7 @@ FP64_VALU_PEAK_TOPS = 39.3  # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz, one o
 # Valid only for the kernel source it was measured on.
 MEASURED_TRAFFIC = {
     "source": "paper_2609_26108_amd/csrc/trace.hip",
-    "source_sha256_16": "75f1a9157b2f5039",
+    "source_sha256_16": "43dc2be1d97c9c55",
     "fetch_scale": 2.0, "write_scale": 1.0,
     "kib_per_dispatch": {  # kernel -> (FETCH_SIZE KiB, WRITE_SIZE KiB)
         "k_relax_tau": (2470.8, 733.7),
@@ -72,7 +72,7 @@ MEASURED_FP64 = {
                 "paper_2609_26108_amd/csrc/physics.h", "paper_2609_26108_amd/csrc/mlp.h"],
     "sources_sha256_16": "78bc2904204b923e",
     "flops_per_dispatch": {"k_warm_solve": 4.9490e11, "k_warm_window": 2.8717e11,
-                           "k_warm_fold": 1.3748e10, "k_warm_predict": 5.3496e9},
+                           "k_warm_fold": 1.3793e10, "k_warm_predict": 5.3496e9},
 }
 
 
