@@ -110,6 +110,8 @@ def parse():
                         "persistent; 2 node frontier")
     p.add_argument("--autotune", action="store_true",
                    help="headline: let the autotuner pick tile, push group, launch and ordering")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="complex2d: trace with the default launch options")
     p.add_argument("--bucket", type=float, default=0.0,
                    help="node-frontier near/far bucket width (units of the smallest weight)")
     p.add_argument("--workload", choices=("layered", "complex2d", "shots", "3d"),
@@ -570,11 +572,26 @@ def run_complex(args):
     # 4. per-node traveltimes through the surrogate-started cache
     grid = C.make_grid(m.nx, m.nz, m.hx, m.hz, m.radius, None)
     stats = C.TraceStats()
-    opts = C.trace_opts(C.OUT_TAU_R | C.OUT_TAU_I | C.OUT_TSTAR | C.OUT_PRED_P, stats=stats,
-                        launch=args.launch, bucket_width=args.bucket)
+    outs = C.OUT_TAU_R | C.OUT_TAU_I | C.OUT_TSTAR | C.OUT_PRED_P
+    opts = C.trace_opts(outs, stats=stats, launch=args.launch, bucket_width=args.bucket)
     S = len(m.sources)
     tr = {k: torch.empty((S, n), dtype=torch.float64, device=dev) for k in ("r", "i", "t")}
     pp = torch.empty((S, n), dtype=torch.int32, device=dev)
+    # launch options for this trace, picked by the autotuner before it is timed
+    if not args.no_autotune:
+        tb = C.Batch()
+        tb.add(desc, warm, n, grid, mode, m.sources, tau_r=tr["r"], tau_i=tr["i"],
+               tstar=tr["t"], pred_p=pp)
+        aws = torch.empty(C.chert_trace_autotune_workspace_bytes(tb, opts), dtype=torch.uint8,
+                          device=dev)
+        C.chert_trace_autotune(tb, opts, aws, stream=stream)
+        out["trace_autotune"] = {"tile": [opts.tile_x, opts.tile_z],
+                                 "push_group": opts.push_group,
+                                 "launch": LAUNCH_NAMES[opts.launch],
+                                 "bucket_width": opts.bucket_width}
+        opts = C.trace_opts(outs, opts.tile_x, opts.tile_z, push_group=opts.push_group,
+                            launch=opts.launch, bucket_width=opts.bucket_width, stats=stats)
+        del aws, tb
     tws = torch.empty(C.chert_trace_workspace_bytes(desc, n, grid, S, opts), dtype=torch.uint8,
                       device=dev)
 
