@@ -145,7 +145,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: there is no multi-GPU path "
               "(shots and cache entries would shard across GPUs with no communication).",
               file=sys.stderr)
         sys.exit(2)
