@@ -620,7 +620,13 @@ static int gcd_int(int a, int b) {
 }
 
 /* Offsets o with max(|ox|,|oz|) <= R and gcd(|ox|,|oz|) = 1, ordered by
- * (oz, ox) ascending.  Returns the count (arrays may be NULL to count). */
+ * (oz, ox) ascending.  Returns the count (arrays may be NULL to count).
+ * bin(o) is the tabulated direction nearest to the edge (eq 27 and the
+ * cache lookup after it).  An edge exactly half-way between two tabulated
+ * directions is decided on the half-plane of angles [0, pi) -- rounding
+ * half away from zero there -- and an offset in the other half-plane takes
+ * the direction opposite to its reverse's, so that an edge and its reverse
+ * always read diametrically opposite directions. */
 int orc_star_2d(int R, double hx, double hz, int n_dirs, int32_t *ox,
                 int32_t *oz, double *L, int32_t *bin) {
   int n = 0;
@@ -633,10 +639,11 @@ int orc_star_2d(int R, double hx, double hz, int n_dirs, int32_t *ox,
         ox[n] = x;
         oz[n] = z;
         L[n] = sqrt(dx * dx + dz * dz);
-        double ang = atan2(dx, dz); /* from +z towards +x */
+        int upper = (x > 0) || (x == 0 && z > 0); /* angle in [0, pi) */
+        double ang = upper ? atan2(dx, dz) : atan2(-dx, -dz); /* from +z to +x */
         long b = lround(ang * n_dirs / (2.0 * ORC_PI));
-        b %= n_dirs;
-        if (b < 0) b += n_dirs;
+        if (!upper) b = b + n_dirs / 2;
+        b = ((b % n_dirs) + n_dirs) % n_dirs;
         bin[n] = (int32_t)b;
       }
       ++n;

@@ -33,6 +33,21 @@ static int gcd_i(int a, int b) {
   return a;
 }
 
+// Nearest tabulated direction of an edge (the cached direction closest to
+// the edge vector).  The bin is rounded on the half of the star with
+// direction angle in [0, pi) (ox > 0, or ox == 0 and oz > 0); the reversed
+// offset takes the diametrically opposite bin, so bin(-o) = bin(o) + n_dirs/2
+// also where the angle falls exactly between two tabulated directions.
+static int32_t star_bin_2d(int x, int z, double hx, double hz, int n_dirs) {
+  const bool canon = x > 0 || (x == 0 && z > 0);
+  const double dx = (canon ? x : -x) * hx, dz = (canon ? z : -z) * hz;
+  long b = lround(atan2(dx, dz) * n_dirs / (2.0 * M_PI));
+  if (!canon) b += n_dirs / 2;
+  b %= n_dirs;
+  if (b < 0) b += n_dirs;
+  return (int32_t)b;
+}
+
 int star_2d(int R, double hx, double hz, int n_dirs, int32_t* ox, int32_t* oz, double* L,
             int32_t* bin) {
   int n = 0;
@@ -44,10 +59,7 @@ int star_2d(int R, double hx, double hz, int n_dirs, int32_t* ox, int32_t* oz, d
         ox[n] = x;
         oz[n] = z;
         L[n] = sqrt(dx * dx + dz * dz);  // eq 27, IEEE sqrt
-        long b = lround(atan2(dx, dz) * n_dirs / (2.0 * M_PI));
-        b %= n_dirs;
-        if (b < 0) b += n_dirs;
-        bin[n] = (int32_t)b;
+        bin[n] = star_bin_2d(x, z, hx, hz, n_dirs);
       }
       ++n;
     }

@@ -1338,7 +1338,9 @@ int validate_job_2d(const chert_trace_job& j, uint32_t outs) {
       ((outs & CHERT_OUT_TSTAR) && !j.tstar_dev) || ((outs & CHERT_OUT_PRED_P) && !j.pred_p_dev) ||
       ((outs & CHERT_OUT_PRED_A) && !j.pred_a_dev))
     return fail(CHERT_ERR_INVALID_ARG, "a selected output is NULL");
-  if (g->class_id_dev && (int64_t)j.n_classes * j.n_classes > ((int64_t)1 << 26))
+  // the tile kernels index a field's class-pair table [K][K][n_off] in 32 bits
+  const int64_t n_off = star_2d(g->radius, 1.0, 1.0, 4, nullptr, nullptr, nullptr, nullptr);
+  if (g->class_id_dev && (int64_t)j.n_classes * j.n_classes * n_off >= ((int64_t)1 << 31))
     return fail(CHERT_ERR_UNSUPPORTED, "class-pair table too large (use one class per node)");
   return CHERT_OK;
 }

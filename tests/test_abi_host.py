@@ -52,10 +52,24 @@ def test_class_from_thomsen_rejects(args):
 def test_star_matches_oracle_bitwise():
     for R in range(1, 9):
         for hx, hz in [(10.0, 10.0), (5.0, 7.5)]:
-            a = C.chert_star_2d(R, hx, hz)
-            b = O.star_2d(R, hx, hz)
-            for x, y in zip(a, b):
-                assert np.array_equal(x, y)
+            for n_dirs in (360, 180, 90, 720, 36):
+                a = C.chert_star_2d(R, hx, hz, n_dirs)
+                b = O.star_2d(R, hx, hz, n_dirs)
+                for x, y in zip(a, b):
+                    assert np.array_equal(x, y)
+
+
+def test_star_subset_closed_at_half_step_ties():
+    """At a 2-degree step the diagonal offsets lie half-way between two
+    directions; the star still reads bin(o) + n_dirs/2 for -o, so its
+    subset is closed under reversal and a per-node cache descriptor with
+    it is accepted."""
+    for R in (1, 3, 5):
+        ox, oz, L, b = C.chert_star_2d(R, 10.0, 10.0, 180)
+        assert np.array_equal(b[::-1], (b + 90) % 180)
+        sub = C.star_subset(R, 10.0, 10.0, 180)
+        d = C.cache_desc(n_dirs=180, modes=(0,), subset=sub)
+        C.chert_cache_layout_of(d, 4)
 
 
 def test_layout():
@@ -282,3 +296,24 @@ def test_surrogate_layout_and_validation():
     with pytest.raises(C.ChertError):  # negative residual tolerance
         C.chert_build_cache_surrogate(d, ok, 100, ok, ok, _Ptr(0x40000, n=need),
                                       resid_tol=-1.0, stream=0)
+
+
+def test_class_pair_table_index_limit():
+    """The tile kernels index one field's class-pair weight table
+    [K][K][|O|] in 32 bits, so K * K * |O| must stay below 2^31: at radius 5
+    (|O| = 80) K = 5181 is accepted and K = 5182 rejected before any device
+    work."""
+    import torch
+    cid = torch.zeros(16, dtype=torch.int32)  # never read: validation fails first
+    grid = C.make_grid(4, 4, 10.0, 10.0, 5, cid)
+    opts = C.trace_opts(C.OUT_TAU_R)
+    d = C.cache_desc(n_dirs=360, modes=(0,))
+    assert 5181 * 5181 * 80 < 2 ** 31 <= 5182 * 5182 * 80
+    assert C.chert_trace_workspace_bytes(d, 5181, grid, 1, opts) > 0
+    assert C.chert_trace_workspace_bytes(d, 5182, grid, 1, opts) == 0
+    b = C.Batch()
+    t = torch.zeros(16, dtype=torch.float64)
+    b.add(d, t, 5182, grid, 0, [0], tau_r=t)
+    with pytest.raises(C.ChertError) as e:
+        C.chert_trace_batch(b, opts, None, stream=0)
+    assert e.value.code == 2

@@ -24,9 +24,18 @@ def py_star(R, hx, hz, n_dirs=360):
                 continue
             offs.append((ox, oz))
     L = [math.sqrt((ox * hx) ** 2 + (oz * hz) ** 2) for ox, oz in offs]
-    b = [round(math.degrees(math.atan2(ox * hx, oz * hz)) * n_dirs / 360.0) % n_dirs
-         for ox, oz in offs]
+    b = [py_bin(ox, oz, hx, hz, n_dirs) for ox, oz in offs]
     return offs, L, b
+
+
+def py_bin(ox, oz, hx, hz, n_dirs):
+    """Nearest of n_dirs equally spaced directions; on an exact tie the
+    half-plane ox > 0 (or ox = 0, oz > 0) rounds up in angle and the other
+    half-plane mirrors it, so bin(-o) = bin(o) + n_dirs/2."""
+    if ox > 0 or (ox == 0 and oz > 0):
+        x = math.degrees(math.atan2(ox * hx, oz * hz)) * n_dirs / 360.0
+        return int(math.floor(x + 0.5)) % n_dirs
+    return (py_bin(-ox, -oz, hx, hz, n_dirs) + n_dirs // 2) % n_dirs
 
 
 def random_cache(K, rng, n_dirs=360, elastic=False):
@@ -74,6 +83,29 @@ def test_star_counts_and_bins():
         ang = np.degrees(np.arctan2(ox, oz))
         frac = np.abs((ang % 1.0) - 0.5)
         assert frac.min() > 0.06  # far from a rounding tie
+
+
+@pytest.mark.parametrize("n_dirs", [360, 180, 90, 720, 36, 4])
+@pytest.mark.parametrize("hx,hz", [(10.0, 10.0), (5.0, 7.5), (10.0, 5.0)])
+def test_star_bins_nearest_and_antipodal(n_dirs, hx, hz):
+    """bin(o) is a nearest tabulated direction of the edge vector (within
+    half a step of its angle) and bin(-o) = bin(o) + n_dirs/2 for every
+    step, including the 2-degree step where edges such as (1, 1) lie
+    exactly half-way between two directions."""
+    for R in range(1, 9):
+        ox, oz, L, b = O.star_2d(R, hx, hz, n_dirs)
+        offs, Lp, bp = py_star(R, hx, hz, n_dirs)
+        np.testing.assert_array_equal(b, bp)
+        step = 2 * np.pi / n_dirs
+        ang = np.arctan2(ox * hx, oz * hz)
+        miss = np.angle(np.exp(1j * (ang - b * step)))
+        assert np.abs(miss).max() <= step / 2 * (1 + 1e-12)
+        n = len(ox)
+        # the star is ordered so that offset n-1-o is -o
+        assert np.array_equal(ox[::-1], -ox) and np.array_equal(oz[::-1], -oz)
+        np.testing.assert_array_equal(b[::-1], (b + n_dirs // 2) % n_dirs)
+        sub = O.star_subset(R, hx, hz, n_dirs)
+        assert set(((sub + n_dirs // 2) % n_dirs).tolist()) == set(sub.tolist())
 
 
 # -------------------------------------------------------- brute force ---
