@@ -27,7 +27,11 @@
  *     queries.
  *   - `stream` is a hipStream_t passed as void*.  Kernels are enqueued on it.
  *     Argument validation happens before anything is enqueued; a validation
- *     failure leaves every output untouched.
+ *     failure leaves every output untouched.  The one check that needs the
+ *     device -- class ids of a class map in range -- runs as the first
+ *     kernel of a trace; a failing map makes every later kernel of the call
+ *     leave at once, so the outputs stay untouched there too, and the call
+ *     (or chert_trace_graph_finish) returns INVALID_ARG.
  */
 #ifndef CHERT_H
 #define CHERT_H
@@ -47,7 +51,8 @@ typedef enum {
   CHERT_ERR_NO_CONVERGENCE = 4,/* relaxation round cap reached            */
   CHERT_ERR_CAPACITY = 5,      /* output buffer too small                 */
   CHERT_ERR_UNREACHABLE = 6,   /* receiver has no predecessor             */
-  CHERT_ERR_CYCLE = 7          /* predecessor chain longer than the grid  */
+  CHERT_ERR_CYCLE = 7,         /* predecessor chain longer than the grid  */
+  CHERT_ERR_ABORTED = 8        /* the caller's abort word was raised      */
 } chert_status;
 
 /* wave modes of the sagittal-plane problem */
@@ -65,8 +70,28 @@ enum {
   CHERT_ST_NO_BRACKET = 1, /* no slowness angle reaches the ray direction   */
   CHERT_ST_ILL = 2,        /* chosen root where |dpsi/dtheta_R| < 1e-2       */
   CHERT_ST_FLUID = 4,      /* shear mode in a class without shear stiffness */
-  CHERT_ST_NONPHYS = 8     /* negative attenuation or non-finite velocity   */
+  CHERT_ST_NONPHYS = 8,    /* negative attenuation or non-finite velocity   */
+  CHERT_ST_NOCONV = 16     /* the chosen root's residual (CHERT_F_RES) is
+                              above the descriptor's resid_tol             */
 };
+/* Entries with NO_BRACKET, FLUID, NONPHYS or NOCONV are unusable: an edge
+ * that reads one is impassable (w = +inf). */
+
+/* Counters of one cache build (device memory, written by the build calls
+ * when chert_cache_desc.stats_dev is set).  Entries are stored columns
+ * (modes in mode_mask x classes x columns, centrosymmetric copies
+ * included). */
+typedef struct chert_cache_stats {
+  int64_t n_entries;    /* stored entries of the built modes                */
+  int64_t n_converged;  /* status OK or ILL only: a root within resid_tol   */
+  int64_t n_fallback;   /* entries of jobs the surrogate-started build sent
+                           back to the full plain solver (0 for plain)      */
+  int64_t n_noconv;     /* CHERT_ST_NOCONV set                               */
+  int64_t n_illcond;    /* CHERT_ST_ILL set                                  */
+  int64_t n_nobracket;  /* CHERT_ST_NO_BRACKET set                           */
+  int64_t n_unusable;   /* FLUID or NONPHYS set                              */
+  double max_resid;     /* largest residual over entries with a root        */
+} chert_cache_stats;
 
 /* One cache class: the stored medium of eq 26 (c_ijkl(k), Q_ijkl(k), rho(k))
  * for a transversely isotropic medium.  Complex moduli follow eq 2:
@@ -128,7 +153,20 @@ typedef struct chert_cache_desc {
                          most 512; only these columns are stored and built
                          (per-node caches need only the star's bins).  Read
                          during the call only.                              */
+  double resid_tol;   /* homogeneity / direction residual above which an
+                         entry gets CHERT_ST_NOCONV; finite, >= 0 (0 = 1e-9) */
+  int32_t max_iter;   /* cap on the refinement steps of each theta_R bracket
+                         (Newton steps, then the halvings of the bisection
+                         fallback); >= 0 (0 = 12 Newton steps and 200
+                         halvings)                                          */
+  int32_t reserved;   /* must be 0                                          */
+  chert_cache_stats *stats_dev; /* nullable device struct: the build calls
+                         overwrite it with their counters (after the
+                         entries, on the same stream)                       */
 } chert_cache_desc;
+/* The trace calls read dim, n_dirs, mode_mask and the subset of a
+ * descriptor; the solver fields (kernel, n_sweep, resid_tol, max_iter,
+ * stats_dev) matter only to the build calls. */
 
 /* Field order of the cache arrays. */
 enum {
@@ -282,6 +320,16 @@ typedef struct chert_trace_opts {
                          + width; otherwise it stays active for a later
                          round.  The fields do not depend on it.          */
   chert_trace_stats *stats_host; /* nullable: filled when the call returns */
+  const volatile int32_t *abort_flag_host; /* nullable caller-owned word in
+                         pinned host memory (hipHostMalloc).  While it is
+                         non-zero the relaxation stops at its next round
+                         boundary: the host checks it between launches, the
+                         persistent and graph-replayed kernels poll it at
+                         every round, and every kernel still exits normally.
+                         The call then returns CHERT_ERR_ABORTED; tau_R and
+                         tau_I hold upper bounds of the fixed point (each
+                         value +inf or the length of some path), predecessor
+                         and t* outputs are unspecified.                    */
 } chert_trace_opts;
 
 /* Scratch needed by chert_trace_field for these arguments. */

@@ -175,10 +175,12 @@ def star_2d(R, hx, hz, n_dirs=360):
     return ox, oz, L, b
 
 
-def trace_2d(nx, nz, hx, hz, class_id, R, V, A, status, src, n_dirs=360, subset=None):
+def trace_2d(nx, nz, hx, hz, class_id, R, V, A, status, src, n_dirs=360, subset=None,
+             attenuation=True):
     """Dijkstra traveltimes for one mode from a cache slice V/A/status
     [K][n_cols].  class_id None: one class per node.  Returns dict of tauR,
-    tauI, predP, predA, tstar, hopP, hopA."""
+    tauI, predP, predA, tstar, hopP, hopA; attenuation=False skips the
+    attenuation field (tauI, predA, hopA come back None)."""
     n = nx * nz
     cid = None
     if class_id is not None:
@@ -190,6 +192,8 @@ def trace_2d(nx, nz, hx, hz, class_id, R, V, A, status, src, n_dirs=360, subset=
     st = np.ascontiguousarray(status, dtype=np.int32)
     out = {k: np.zeros(n) for k in ("tauR", "tauI", "tstar")}
     out.update({k: np.zeros(n, np.int32) for k in ("predP", "predA", "hopP", "hopA")})
+    if not attenuation:
+        out.update(tauI=None, predA=None, hopA=None)
     rc = lib().orc_trace_2d_cols(nx, nz, hx, hz, _p(cid), R, n_dirs, _p(sub),
                                  0 if sub is None else sub.size, _p(V), _p(A),
                                  _p(st), int(src), _p(out["tauR"]), _p(out["tauI"]),
@@ -263,17 +267,20 @@ def star_3d(R, hx, hy, hz, N=N_FIB):
     return ox, oy, oz, L, b
 
 
-def trace_3d(nx, ny, nz, hx, hy, hz, class_id, R, V, A, status, src, N=N_FIB):
+def trace_3d(nx, ny, nz, hx, hy, hz, class_id, R, V, A, status, src, N=N_FIB,
+             outputs=("tauR", "tauI", "predP", "predA", "tstar")):
     """Dijkstra (tauR, tauI, predP, predA, tstar) on a 3D grid; node
-    ix + nx (iy + ny iz); t* folds the attenuation weights along predP."""
+    ix + nx (iy + ny iz); t* folds the attenuation weights along predP.
+    Only the named outputs are computed (the others come back None)."""
     n = nx * ny * nz
     cid = np.ascontiguousarray(class_id, dtype=np.int32).reshape(-1)
     assert cid.size == n
     V = np.ascontiguousarray(V, dtype=np.float64)
     A = np.ascontiguousarray(A, dtype=np.float64)
     st = np.ascontiguousarray(status, dtype=np.int32)
-    out = {k: np.zeros(n) for k in ("tauR", "tauI", "tstar")}
-    out.update({k: np.zeros(n, np.int32) for k in ("predP", "predA")})
+    out = {k: (np.zeros(n) if k in outputs else None) for k in ("tauR", "tauI", "tstar")}
+    out.update({k: (np.zeros(n, np.int32) if k in outputs else None)
+                for k in ("predP", "predA")})
     rc = lib().orc_trace_3d(nx, ny, nz, hx, hy, hz, _p(cid), R, N, _p(V), _p(A), _p(st),
                             int(src), _p(out["tauR"]), _p(out["tauI"]), _p(out["predP"]),
                             _p(out["predA"]), _p(out["tstar"]))

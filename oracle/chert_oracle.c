@@ -57,7 +57,8 @@ enum {
   ORC_ST_NO_BRACKET = 1,  /* no slowness angle reaches the target ray direction */
   ORC_ST_ILL = 2,         /* chosen root sits where d(psi)/d(theta_R) is tiny  */
   ORC_ST_FLUID = 4,       /* shear mode in a medium without shear stiffness     */
-  ORC_ST_NONPHYS = 8      /* negative attenuation or non-finite ray quantities  */
+  ORC_ST_NONPHYS = 8,     /* negative attenuation or non-finite ray quantities  */
+  ORC_ST_NOCONV = 16      /* the root's residual is above ORC_RESID_TOL          */
 };
 
 /* output fields of one cache entry */
@@ -69,6 +70,7 @@ enum { F_V = 0, F_A, F_Q, F_RX, F_RZ, F_THR, F_THI, F_RES, ORC_NF };
 #define ORC_THR_TOL 1e-14                    /* bisection width for theta_R  */
 #define ORC_ILL_SLOPE 1e-2                   /* |dpsi/dtheta_R| flag level   */
 #define ORC_TIE_REL 1e-12                    /* equal ray velocities         */
+#define ORC_RESID_TOL 1e-9                   /* converged-root residual cap  */
 
 /* ------------------------------------------------------------------------ */
 /* O-1  constitutive step (eq 2; Thomsen 1986 for the real part)           */
@@ -577,6 +579,7 @@ int orc_build_cache_2d_cols(const double *classes, long n_classes, int n_dirs,
           continue;
         }
         if (!(e.A >= 0.0) || !isfinite(e.V) || !(e.V > 0.0)) st |= ORC_ST_NONPHYS;
+        if (!(e.res <= ORC_RESID_TOL)) st |= ORC_ST_NOCONV;
         write_entry(fields, stride, e0, &e, m.tilt);
         status[e0] = st;
         /* centrosymmetric copy: the reversed ray direction has the same
@@ -725,7 +728,7 @@ static long class_of(const graph_t *g, long node) {
 
 static int entry_usable(const graph_t *g, long k, int c) {
   int32_t s = g->st[k * g->n_cols + c];
-  return !(s & (ORC_ST_NO_BRACKET | ORC_ST_FLUID | ORC_ST_NONPHYS));
+  return !(s & (ORC_ST_NO_BRACKET | ORC_ST_FLUID | ORC_ST_NONPHYS | ORC_ST_NOCONV));
 }
 
 /* eq 29 / eq 30 with endpoint averages (eq 28); field 0 = propagation,
@@ -881,9 +884,11 @@ int orc_trace_2d_cols(long nx, long nz, double hx, double hz,
                .ny = 1, .oy = NULL, .L = L, .cls = class_id,
                .n_cols = subset ? n_subset : n_dirs, .col = col, .V = V, .A = A, .st = st};
   long nrP = 0, nrA = 0;
-  if (dijkstra(&g, 0, src, tR) || dijkstra(&g, 1, src, tI)) { rc = 2; goto out; }
+  /* the attenuation field is solved only when one of its outputs is asked for */
+  int want_att = tauI || predA || hopA;
+  if (dijkstra(&g, 0, src, tR) || (want_att && dijkstra(&g, 1, src, tI))) { rc = 2; goto out; }
   predecessors(&g, 0, src, tR, pP, hP, ordP, &nrP);
-  predecessors(&g, 1, src, tI, pA, hA, ordA, &nrA);
+  if (want_att) predecessors(&g, 1, src, tI, pA, hA, ordA, &nrA);
   if (tstar) {
     /* t*: attenuation folded along the propagation raypath tree, source
      * outwards in BFS order so each parent is final first */
@@ -945,6 +950,7 @@ static int solve_bin_fresh(const double *cls, int mode, int reading,
   free(tab);
   if (st & ORC_ST_NO_BRACKET) return st;
   if (!(e.A >= 0.0) || !isfinite(e.V) || !(e.V > 0.0)) st |= ORC_ST_NONPHYS;
+  if (!(e.res <= ORC_RESID_TOL)) st |= ORC_ST_NOCONV;
   *V = e.V;
   *A = e.A;
   return st;
@@ -986,7 +992,7 @@ int orc_trace_uncached_2d(long nx, long nz, double hx, double hz,
       int sv = solve_bin_fresh(classes + 13 * class_id[v], mode, reading,
                                n_sweep, n_dirs, bin[o], &Vv, &Av);
       solves += 2;
-      int bad = ORC_ST_NO_BRACKET | ORC_ST_FLUID | ORC_ST_NONPHYS;
+      int bad = ORC_ST_NO_BRACKET | ORC_ST_FLUID | ORC_ST_NONPHYS | ORC_ST_NOCONV;
       double w;
       if ((su & bad) || (sv & bad)) w = INFINITY;
       else if (field == 0) w = L[o] / (0.5 * (Vu + Vv));
@@ -1113,6 +1119,7 @@ int orc_build_cache_3d(const double *classes, long n_classes, int N,
           continue;
         }
         if (!(e.A >= 0.0) || !isfinite(e.V) || !(e.V > 0.0)) st |= ORC_ST_NONPHYS;
+        if (!(e.res <= ORC_RESID_TOL)) st |= ORC_ST_NOCONV;
         fields[F_V * stride + idx] = e.V;
         fields[F_A * stride + idx] = e.A;
         fields[F_Q * stride + idx] = e.Q;

@@ -19,10 +19,11 @@ LIB_PATH = os.path.join(HERE, "libchert.so")
 
 CHERT_OK = 0
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "HIP",
-                4: "NO_CONVERGENCE", 5: "CAPACITY", 6: "UNREACHABLE", 7: "CYCLE"}
+                4: "NO_CONVERGENCE", 5: "CAPACITY", 6: "UNREACHABLE", 7: "CYCLE", 8: "ABORTED"}
 QP, QSV, QSH = 0, 1, 2
 KERNEL_MEV, KERNEL_OEV = 0, 1
-ST_OK, ST_NO_BRACKET, ST_ILL, ST_FLUID, ST_NONPHYS = 0, 1, 2, 4, 8
+ST_OK, ST_NO_BRACKET, ST_ILL, ST_FLUID, ST_NONPHYS, ST_NOCONV = 0, 1, 2, 4, 8, 16
+ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_NO_CONVERGENCE, ERR_ABORTED = 1, 2, 4, 8
 FIELDS = ("V", "A", "Q", "rx", "rz", "thR", "thI", "res")
 NF = len(FIELDS)
 OUT_TAU_R, OUT_TAU_I, OUT_TSTAR, OUT_PRED_P, OUT_PRED_A = 1, 2, 4, 8, 16
@@ -66,11 +67,26 @@ class ChertClass(ctypes.Structure):
         return np.array([getattr(self, n) for n, _ in self._fields_])
 
 
+class CacheStats(ctypes.Structure):
+    _fields_ = [("n_entries", ctypes.c_int64), ("n_converged", ctypes.c_int64),
+                ("n_fallback", ctypes.c_int64), ("n_noconv", ctypes.c_int64),
+                ("n_illcond", ctypes.c_int64), ("n_nobracket", ctypes.c_int64),
+                ("n_unusable", ctypes.c_int64), ("max_resid", ctypes.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+CACHE_STATS_BYTES = ctypes.sizeof(CacheStats)
+
+
 class CacheDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n_dirs", ctypes.c_int32),
                 ("mode_mask", ctypes.c_uint32), ("kernel", ctypes.c_int32),
                 ("n_sweep", ctypes.c_int32), ("n_subset", ctypes.c_int32),
-                ("subset_host", ctypes.c_void_p)]
+                ("subset_host", ctypes.c_void_p), ("resid_tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("stats_dev", ctypes.c_void_p)]
 
     @property
     def n_cols(self):
@@ -115,7 +131,8 @@ class TraceOpts(ctypes.Structure):
     _fields_ = [("outputs", ctypes.c_uint32), ("tile_x", ctypes.c_int32),
                 ("tile_z", ctypes.c_int32), ("max_rounds", ctypes.c_int32),
                 ("push_group", ctypes.c_int32), ("launch", ctypes.c_int32),
-                ("bucket_width", ctypes.c_double), ("stats_host", ctypes.c_void_p)]
+                ("bucket_width", ctypes.c_double), ("stats_host", ctypes.c_void_p),
+                ("abort_flag_host", ctypes.c_void_p)]
 
 
 class SurrogateLayout(ctypes.Structure):
@@ -223,18 +240,33 @@ def chert_class_from_thomsen(vp0, vs0, rho, eps, delta, gamma, tilt, azimuth, qp
 
 
 def cache_desc(n_dirs=360, modes=(QP, QSV, QSH), kernel=KERNEL_MEV, n_sweep=1440, dim=2,
-               subset=None):
+               subset=None, resid_tol=0.0, max_iter=0, stats=None):
     """subset: ascending direction indices closed under reversal (kept
-    referenced by the descriptor), e.g. star_subset(radius, hx, hz)."""
+    referenced by the descriptor), e.g. star_subset(radius, hx, hz);
+    resid_tol / max_iter: the solver's residual cap and bracket step cap
+    (0 = library defaults); stats: a device tensor of at least
+    CACHE_STATS_BYTES bytes that the build calls overwrite with a
+    chert_cache_stats (read it with cache_stats_of)."""
     mask = 0
     for m in modes:
         mask |= 1 << m
+    sp = stats.data_ptr() if stats is not None else None
     if subset is None:
-        return CacheDesc(dim, n_dirs, mask, kernel, n_sweep, 0, None)
-    sub = np.ascontiguousarray(subset, dtype=np.int32)
-    d = CacheDesc(dim, n_dirs, mask, kernel, n_sweep, int(sub.size), sub.ctypes.data)
-    d._subset = sub
+        d = CacheDesc(dim, n_dirs, mask, kernel, n_sweep, 0, None, float(resid_tol),
+                      int(max_iter), 0, sp)
+    else:
+        sub = np.ascontiguousarray(subset, dtype=np.int32)
+        d = CacheDesc(dim, n_dirs, mask, kernel, n_sweep, int(sub.size), sub.ctypes.data,
+                      float(resid_tol), int(max_iter), 0, sp)
+        d._subset = sub
+    d._stats = stats
     return d
+
+
+def cache_stats_of(stats_dev):
+    """chert_cache_stats from the device tensor a build wrote (synchronises)."""
+    raw = bytes(stats_dev[:CACHE_STATS_BYTES].cpu().numpy().tobytes())
+    return CacheStats.from_buffer_copy(raw)
 
 
 def star_subset(radius, hx, hz, n_dirs=360):
@@ -333,14 +365,18 @@ def make_grid(nx, nz, hx, hz, radius, class_id_dev):
 
 
 def trace_opts(outputs=OUT_ALL, tile_x=0, tile_z=0, max_rounds=0, stats=None, push_group=0,
-               launch=0, bucket_width=0.0):
+               launch=0, bucket_width=0.0, abort_flag=None):
     """stats: a TraceStats to fill (kept referenced by the returned options);
     launch: LAUNCH_PER_ROUND, LAUNCH_PERSISTENT (2D tiles) or LAUNCH_FRONTIER
     (node frontier; always used in 3D); bucket_width: near/far bucket width
-    of the frontier iteration (units of the smallest edge weight)."""
+    of the frontier iteration (units of the smallest edge weight);
+    abort_flag: a pinned host int32 tensor (torch pin_memory) whose first
+    element, once non-zero, stops the relaxation (CHERT_ERR_ABORTED)."""
     o = TraceOpts(outputs, tile_x, tile_z, max_rounds, push_group, launch, float(bucket_width),
-                  ctypes.addressof(stats) if stats is not None else None)
+                  ctypes.addressof(stats) if stats is not None else None,
+                  abort_flag.data_ptr() if abort_flag is not None else None)
     o._stats = stats
+    o._abort = abort_flag
     return o
 
 

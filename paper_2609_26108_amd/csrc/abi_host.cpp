@@ -312,6 +312,10 @@ extern "C" int chert_cache_layout_of(const chert_cache_desc* d, int64_t n_classe
     return fail(CHERT_ERR_INVALID_ARG, "bad kernel");
   if (d->n_sweep < 16) return fail(CHERT_ERR_INVALID_ARG, "n_sweep must be >= 16");
   if (n_classes <= 0) return fail(CHERT_ERR_INVALID_ARG, "n_classes must be positive");
+  if (!(d->resid_tol >= 0.0) || !isfinite(d->resid_tol))
+    return fail(CHERT_ERR_INVALID_ARG, "resid_tol must be finite and >= 0");
+  if (d->max_iter < 0) return fail(CHERT_ERR_INVALID_ARG, "max_iter must be >= 0");
+  if (d->reserved != 0) return fail(CHERT_ERR_INVALID_ARG, "reserved field must be 0");
   if (d->n_subset != 0) {
     if (d->n_subset < 0 || d->n_subset > kMaxSubset || !d->subset_host || (d->n_subset & 1))
       return fail(CHERT_ERR_INVALID_ARG, "subset needs 2..512 (even) directions");

@@ -92,6 +92,9 @@ struct SolveArgs {
   int dim;          // 2, or 3: columns are Fibonacci ray directions
   double fib_ga;    // 3D: golden angle pi (3 - sqrt 5) of the direction set
   int subset;       // 0: every direction d < n_dirs/2, column d, copy at d + n_dirs/2
+  double resid_tol;  // entries whose residual is above this get CHERT_ST_NOCONV
+  int newton_iters;  // Newton steps per bracket
+  int bisect_iters;  // halvings of the bisection fallback
   int16_t dir[kMaxSubset / 2];   // solved direction (subset caches)
   int16_t col[kMaxSubset / 2];   // its column
   int16_t pcol[kMaxSubset / 2];  // column of the reversed direction
@@ -138,7 +141,7 @@ __device__ __forceinline__ double polar_to_axis(const double3& f, const chert_cl
 __device__ __forceinline__ bool newton_root(const Medium& m, int mode, int kernel,
                                          double psi_star, double ta, double tb,
                                          double ya, double yb, double fa, double fb,
-                                         double* xo, double* yo) {
+                                         int iters, double* xo, double* yo) {
   const bool el = theta_i_zero(m, mode);
   const double eps = kFdEps;
   const double dth = tb - ta;
@@ -146,7 +149,7 @@ __device__ __forceinline__ bool newton_root(const Medium& m, int mode, int kerne
   double x = ta + t * dth;
   double y = el ? 0.0 : ya + t * (yb - ya);
   double last = 1.0;
-  for (int it = 0; it < 12; ++it) {
+  for (int it = 0; it < iters; ++it) {
     const Trig t0 = trig_of(x, y);
     Vel v0 = energy_velocity_t(m, mode, kernel, t0);
     double F2 = wrap_pi(ray_angle(v0) - psi_star);
@@ -184,10 +187,10 @@ __device__ __forceinline__ bool newton_root(const Medium& m, int mode, int kerne
 // trial point (slow, used only when Newton does not settle).
 __device__ __forceinline__ bool bisect_root(const Medium& m, int mode, int kernel,
                                          double psi_star, double ta, double tb, double fa,
-                                         double* xo, double* yo) {
+                                         int iters, double* xo, double* yo) {
   double lo = ta, hi = tb;
   bool neg_lo = fa < 0.0;
-  for (int it = 0; it < 200 && hi - lo > 1e-14; ++it) {
+  for (int it = 0; it < iters && hi - lo > 1e-14; ++it) {
     double mid = 0.5 * (lo + hi);
     double thI, sr, cr;
     sincos(mid, &sr, &cr);
@@ -273,8 +276,9 @@ __device__ __forceinline__ bool bracket_root(const SolveArgs& a, const Medium& m
   double ta = (j + 0.5) * dth;
   double tb = ta + dth;
   double x, y;
-  bool ok = newton_root(m, mode, a.kernel, psi_star, ta, tb, sa.x, sb.x, fa, fb, &x, &y);
-  if (!ok) ok = bisect_root(m, mode, a.kernel, psi_star, ta, tb, fa, &x, &y);
+  bool ok = newton_root(m, mode, a.kernel, psi_star, ta, tb, sa.x, sb.x, fa, fb, a.newton_iters,
+                        &x, &y);
+  if (!ok) ok = bisect_root(m, mode, a.kernel, psi_star, ta, tb, fa, a.bisect_iters, &x, &y);
   if (!ok) return false;
   if (x >= kTwoPi) x -= kTwoPi;
   if (x < 0.0) x += kTwoPi;
@@ -386,6 +390,7 @@ __device__ __forceinline__ void store_pair(const SolveArgs& a, int64_t row, int 
     store_invalid(a, row + pcol, stride, st);
     return;
   }
+  if (!(best.res <= a.resid_tol)) st |= CHERT_ST_NOCONV;
   store_entry(a, row + col, stride, best, tilt, st);
   Entry r = best;
   r.thR = best.thR + kPi;
@@ -403,6 +408,7 @@ __device__ __forceinline__ void store_single(const SolveArgs& a, int64_t idx, in
     store_invalid(a, idx, stride, st);
     return;
   }
+  if (!(best.res <= a.resid_tol)) st |= CHERT_ST_NOCONV;
   double* fl = a.fields;
   fl[CHERT_F_V * stride + idx] = best.V;
   fl[CHERT_F_A * stride + idx] = best.A;
@@ -1120,6 +1126,88 @@ __global__ void k_write_header(uint8_t* cache, int32_t dim, int32_t n_dirs, uint
   }
 }
 
+__global__ void k_cache_stats_zero(chert_cache_stats* st) {
+  if (threadIdx.x == 0) *st = chert_cache_stats{};
+}
+
+__device__ __forceinline__ long long wave_sum(long long v) {
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+  return v;
+}
+__device__ __forceinline__ unsigned long long wave_max(unsigned long long v) {
+  for (int d = 32; d >= 1; d >>= 1) {
+    const unsigned long long o = __shfl_xor(v, d);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Counters of a built cache (chert_cache_stats) from its status and residual
+// arrays, over the modes of the mask; fb_len (nullable) is the number of
+// jobs the surrogate-started build re-solved with the plain solver.
+__global__ void __launch_bounds__(256) k_cache_stats(const int32_t* status, const double* res,
+                                                     int64_t per_mode, uint32_t mask,
+                                                     const int32_t* fb_len, int64_t cols_per_job,
+                                                     chert_cache_stats* st) {
+  long long n = 0, conv = 0, noconv = 0, ill = 0, nob = 0, unus = 0;
+  unsigned long long mr = 0ull;  // non-negative doubles order as their bits
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int m = 0; m < 3; ++m) {
+    if (!(mask & (1u << m))) continue;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < per_mode; t += stride) {
+      const int64_t e = m * per_mode + t;
+      const int32_t sv = status[e];
+      ++n;
+      if ((sv & ~CHERT_ST_ILL) == 0) ++conv;
+      if (sv & CHERT_ST_NOCONV) ++noconv;
+      if (sv & CHERT_ST_ILL) ++ill;
+      if (sv & CHERT_ST_NO_BRACKET) ++nob;
+      if (sv & (CHERT_ST_FLUID | CHERT_ST_NONPHYS)) ++unus;
+      if (!(sv & (CHERT_ST_NO_BRACKET | CHERT_ST_FLUID))) {
+        const double r = fabs(res[e]);
+        if (r >= 0.0) {  // not NaN
+          const unsigned long long b = (unsigned long long)__double_as_longlong(r);
+          mr = b > mr ? b : mr;
+        }
+      }
+    }
+  }
+  n = wave_sum(n);
+  conv = wave_sum(conv);
+  noconv = wave_sum(noconv);
+  ill = wave_sum(ill);
+  nob = wave_sum(nob);
+  unus = wave_sum(unus);
+  mr = wave_max(mr);
+  if (__lane_id() == 0) {
+    atomicAdd((unsigned long long*)&st->n_entries, (unsigned long long)n);
+    atomicAdd((unsigned long long*)&st->n_converged, (unsigned long long)conv);
+    atomicAdd((unsigned long long*)&st->n_noconv, (unsigned long long)noconv);
+    atomicAdd((unsigned long long*)&st->n_illcond, (unsigned long long)ill);
+    atomicAdd((unsigned long long*)&st->n_nobracket, (unsigned long long)nob);
+    atomicAdd((unsigned long long*)&st->n_unusable, (unsigned long long)unus);
+    atomicMax((unsigned long long*)&st->max_resid, mr);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    st->n_fallback = fb_len ? (int64_t)*fb_len * cols_per_job : 0;
+}
+
+// Enqueue the counters of a build into d->stats_dev (if set).
+static void enqueue_cache_stats(const chert_cache_desc* d, int64_t n_classes, uint8_t* cache,
+                                const chert_cache_layout& lay, const int32_t* fb_len,
+                                hipStream_t s) {
+  if (!d->stats_dev) return;
+  const int n_cols = d->n_subset ? d->n_subset : d->n_dirs;
+  const int64_t per_mode = n_classes * (int64_t)n_cols;
+  const int32_t* status = (const int32_t*)(cache + lay.status_offset);
+  const double* res = (const double*)(cache + lay.fields_offset) + CHERT_F_RES * 3 * per_mode;
+  int64_t blocks = (per_mode + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  CHERT_LAUNCH("k_cache_stats_zero", k_cache_stats_zero, dim3(1), dim3(64), 0, s, d->stats_dev);
+  CHERT_LAUNCH("k_cache_stats", k_cache_stats, dim3((unsigned)blocks), dim3(256), 0, s, status,
+               res, per_mode, d->mode_mask, fb_len, (int64_t)n_cols, d->stats_dev);
+}
+
 }  // namespace chert
 
 using namespace chert;
@@ -1150,6 +1238,9 @@ static SolveArgs solve_args(const chert_cache_desc* d, const chert_class* classe
   const int half = d->n_dirs / 2;
   so.dim = d->dim;
   so.fib_ga = M_PI * (3.0 - sqrt(5.0));
+  so.resid_tol = d->resid_tol > 0.0 ? d->resid_tol : 1e-9;
+  so.newton_iters = d->max_iter > 0 ? d->max_iter : 12;
+  so.bisect_iters = d->max_iter > 0 ? d->max_iter : 200;
   if (d->dim == 3) {
     so.subset = 0;
     so.n_cols = d->n_dirs;
@@ -1246,6 +1337,7 @@ extern "C" int chert_build_cache(const chert_cache_desc* d, const chert_class* c
       CHERT_LAUNCH("k_solve", k_solve<1>, dim3((unsigned)(jobs * chunks)), dim3(64),
                    (size_t)d->n_sweep * sizeof(double2), s, so);
   }
+  enqueue_cache_stats(d, n_classes, cache, lay, nullptr, s);
   return launch_status();
 }
 
@@ -1327,5 +1419,6 @@ extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
                  (size_t)d->n_sweep * sizeof(double2), s, w.so, (const int32_t*)w.fb_list,
                  (const int32_t*)w.fb_len, jobs);
   }
+  enqueue_cache_stats(d, n_classes, cache, lay, w.fb_len, s);
   return launch_status();
 }

@@ -78,7 +78,11 @@ int tiles3d_bytes(const Tile3Job* jobs, int n_jobs, const Tile3Prob* probs, int 
 int relax_tiles_3d(const Tile3Job* jobs, int n_jobs, const Tile3Prob* probs, int n_prob,
                    const int32_t* ox_dev, const int32_t* oy_dev, const int32_t* oz_dev, int n_off,
                    int R, int tile_x, int tile_z, int push_group, int max_rounds, void* ws,
-                   size_t ws_bytes, hipStream_t s, int* rounds, int64_t* visits, int64_t* edges);
+                   size_t ws_bytes, hipStream_t s, const volatile int32_t* abort_flag,
+                   int* rounds, int64_t* visits, int64_t* edges);
+
+// Raise *err if any of the n class ids lies outside [0, K) (trace.hip).
+int enqueue_class_check(const int32_t* cls, int64_t n, int K, int32_t* err, hipStream_t s);
 
 // 2D job checks shared by the tile and frontier paths (trace.hip).
 int validate_job_2d(const chert_trace_job& j, uint32_t outs);

@@ -59,7 +59,7 @@ __global__ void k_front_weights(double* W, int K, int n_off, const double* V, co
     const int ki = (int)(r % K);
     const int f = (int)(r / K);
     const int b = col[o];
-    const int bad = CHERT_ST_NO_BRACKET | CHERT_ST_FLUID | CHERT_ST_NONPHYS;
+    const int bad = CHERT_ST_NO_BRACKET | CHERT_ST_FLUID | CHERT_ST_NONPHYS | CHERT_ST_NOCONV;
     const int64_t ei = (int64_t)ki * n_cols + b, ej = (int64_t)kj * n_cols + b;
     double w;
     if ((st[ei] & bad) || (st[ej] & bad)) w = INFINITY;
@@ -734,6 +734,22 @@ int trace_batch_frontier(const chert_trace_job* jobs, int n_jobs, const chert_tr
   a.R = P.R;
   CHERT_LAUNCH("k_front_clear", k_front_clear, dim3(64), dim3(256), 0, s, a.counts,
                P.max_iter + 2, a.err, a.stats);
+  // class ids checked before any output is written
+  {
+    bool any_map = false;
+    for (int j = 0; j < n_jobs; ++j)
+      if (!jd[j].per_node) {
+        enqueue_class_check(jd[j].cls, jd[j].n, jd[j].K, a.err, s);
+        any_map = true;
+      }
+    if (any_map) {
+      int32_t herr0 = 0;
+      e = hipMemcpyAsync(&herr0, a.err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+      if (herr0) return fail(CHERT_ERR_INVALID_ARG, "class id out of range");
+    }
+  }
   enqueue_wmin_init(a.wmin, s);
   if (a.far) {
     for (int j = 0; j < n_jobs; ++j) {
@@ -762,7 +778,8 @@ int trace_batch_frontier(const chert_trace_job* jobs, int n_jobs, const chert_tr
     int rounds = 0;
     rc = relax_tiles_3d(tj.data(), n_jobs, tp.data(), (int)tp.size(), a.ox, a.oy, a.oz, P.n_off,
                         P.R, o->tile_x, o->tile_z, o->push_group, P.max_iter, ws + P.off_tiles,
-                        P.total - P.off_tiles, s, &rounds, &tile_visits, &tile_edges);
+                        P.total - P.off_tiles, s, o->abort_flag_host, &rounds, &tile_visits,
+                        &tile_edges);
     if (rc) return rc;
     iters = rounds;
   }
@@ -777,6 +794,8 @@ int trace_batch_frontier(const chert_trace_job* jobs, int n_jobs, const chert_tr
                          hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+    if (o->abort_flag_host && *o->abort_flag_host)
+      return fail(CHERT_ERR_ABORTED, "aborted by the caller");
     int empty = -1;
     for (int q = 0; q < nb && empty < 0; ++q)
       if (counts[q] == 0) empty = it + q + 1;
@@ -814,6 +833,8 @@ int trace_batch_frontier(const chert_trace_job* jobs, int n_jobs, const chert_tr
       e = hipMemcpyAsync(counts, a.counts + k + 1, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+      if (o->abort_flag_host && *o->abort_flag_host)
+        return fail(CHERT_ERR_ABORTED, "aborted by the caller");
       for (int q = 0; q < nb && layers == 0; ++q)
         if (counts[q] == 0) layers = k + q + 1;
     }

@@ -416,7 +416,8 @@ int tiles3d_bytes(const Tile3Job* jobs, int n_jobs, const Tile3Prob* probs, int 
 int relax_tiles_3d(const Tile3Job* jobs, int n_jobs, const Tile3Prob* probs, int n_prob,
                    const int32_t* ox_dev, const int32_t* oy_dev, const int32_t* oz_dev, int n_off,
                    int R, int tile_x, int tile_z, int push_group, int max_rounds, void* ws,
-                   size_t ws_bytes, hipStream_t s, int* rounds, int64_t* visits, int64_t* edges) {
+                   size_t ws_bytes, hipStream_t s, const volatile int32_t* abort_flag,
+                   int* rounds, int64_t* visits, int64_t* edges) {
   T3Plan P;
   int rc = plan_t3(jobs, n_jobs, probs, n_prob, R, n_off, tile_x, tile_z, max_rounds, &P);
   if (rc) return rc;
@@ -500,6 +501,10 @@ int relax_tiles_3d(const Tile3Job* jobs, int n_jobs, const Tile3Prob* probs, int
     if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
     for (int q = 0; q < nb && done < 0; ++q)
       if (counts[q] == 0) done = r + q + 1;
+    if (done < 0 && abort_flag && *abort_flag) {
+      *rounds = r + nb;
+      return fail(CHERT_ERR_ABORTED, "aborted by the caller");
+    }
   }
   int32_t herr = 0;
   unsigned long long hs[2] = {0, 0};

@@ -126,6 +126,11 @@ struct RelaxArgs {
   unsigned long long* pmin;  // [3][n_prob] smallest key per problem, by round mod 3
   const double* wmin;        // [2] smallest positive edge weight per field
   double bucket;             // 0: every active tile is visited
+  // Caller's abort word (device view of pinned host memory, nullable) and
+  // the device word that records it was seen: rounds after that leave at
+  // once.
+  const int32_t* abort_host;
+  int32_t* abort_seen;
 };
 
 constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;
@@ -148,6 +153,8 @@ __device__ __forceinline__ void count_visit(const RelaxArgs& a, int phase, long 
 
 // ------------------------------------------------------------- weights ---
 
+__global__ void k_check_classes(const int32_t* cls, int64_t n, int K, int32_t* err);
+
 // W[f][ki][kj][o]: eqs 28-30 in this operation order, no contraction.
 __global__ void k_weights(double* W, int K, int n_off, const double* V, const double* A,
                           const int32_t* st, int n_cols, const double* L,
@@ -162,7 +169,7 @@ __global__ void k_weights(double* W, int K, int n_off, const double* V, const do
     int ki = (int)(r % K);
     int f = (int)(r / K);
     const int b = col[o];
-    const int bad = CHERT_ST_NO_BRACKET | CHERT_ST_FLUID | CHERT_ST_NONPHYS;
+    const int bad = CHERT_ST_NO_BRACKET | CHERT_ST_FLUID | CHERT_ST_NONPHYS | CHERT_ST_NOCONV;
     int64_t ei = (int64_t)ki * n_cols + b, ej = (int64_t)kj * n_cols + b;
     double w;
     if ((st[ei] & bad) || (st[ej] & bad)) {
@@ -195,7 +202,7 @@ __global__ void k_weights_node(double* W, int nx, int nz, int n_off, const int32
     if (ix >= 0 && ix < nx && iz >= 0 && iz < nz) {
       const int64_t i = (int64_t)ix + (int64_t)nx * iz;
       const int64_t ei = i * n_cols + col[o], ej = j * n_cols + col[o];
-      const int bad = CHERT_ST_NO_BRACKET | CHERT_ST_FLUID | CHERT_ST_NONPHYS;
+      const int bad = CHERT_ST_NO_BRACKET | CHERT_ST_FLUID | CHERT_ST_NONPHYS | CHERT_ST_NOCONV;
       if (!(st[ei] & bad) && !(st[ej] & bad)) {
         wr = __ddiv_rn(L[o], __dmul_rn(0.5, __dadd_rn(V[ei], V[ej])));
         wi = __dmul_rn(L[o], __dmul_rn(0.5, __dadd_rn(A[ei], A[ej])));
@@ -204,6 +211,13 @@ __global__ void k_weights_node(double* W, int nx, int nz, int n_off, const int32
     W[t] = wr;
     W[total + t] = wi;
   }
+}
+
+int enqueue_class_check(const int32_t* cls, int64_t n, int K, int32_t* err, hipStream_t s) {
+  const int64_t blocks = (n + 255) / 256 > 1024 ? 1024 : (n + 255) / 256;
+  CHERT_LAUNCH("k_check_classes", k_check_classes, dim3((unsigned)(blocks < 1 ? 1 : blocks)),
+               dim3(256), 0, s, cls, n, K, err);
+  return CHERT_OK;
 }
 
 int enqueue_weights_node_2d(double* W, int nx, int nz, int n_off, const int32_t* ox_dev,
@@ -220,16 +234,35 @@ int enqueue_weights_node_2d(double* W, int nx, int nz, int n_off, const int32_t*
 
 // ---------------------------------------------------------------- init ---
 
+// First kernel of a trace: clear the error word, the counters, the phase
+// results and the abort record.
+__global__ void k_trace_begin(int32_t* err, unsigned long long* stats, int32_t* persist_result,
+                              int32_t* abort_seen) {
+  if (threadIdx.x == 0) {
+    *err = 0;
+    *abort_seen = 0;
+  }
+  if (threadIdx.x < 4) persist_result[threadIdx.x] = 0;
+  if (threadIdx.x < 12) stats[threadIdx.x] = 0ull;
+}
+
+// Class ids of a map outside [0, K): raise the error word, which every
+// later kernel of the trace checks before touching an output.
+__global__ void k_check_classes(const int32_t* cls, int64_t n, int K, int32_t* err) {
+  bool bad = false;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t k = cls[j];
+    bad |= k < 0 || k >= K;
+  }
+  if (__ballot(bad) != 0ull && __lane_id() == 0) atomicOr(err, 1);
+}
+
 // blockIdx.y = problem; x strides over its nodes
-__global__ void k_init_fields(const ProbDev* probs, const JobDev* jobs, int32_t* err,
-                              unsigned long long* stats, int32_t* persist_result) {
+__global__ void k_init_fields(const ProbDev* probs, const JobDev* jobs, const int32_t* err) {
+  if (*err) return;  // bad class map: outputs stay untouched
   const ProbDev pr = probs[blockIdx.y];
   const int64_t n = (int64_t)jobs[pr.job].nx * jobs[pr.job].nz;
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 12) {
-    if (threadIdx.x == 0) *err = 0;
-    if (threadIdx.x < 4) persist_result[threadIdx.x] = 0;
-    stats[threadIdx.x] = 0ull;
-  }
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * blockDim.x) {
     pr.tau[j] = (j == pr.src) ? 0.0 : INFINITY;
@@ -253,9 +286,10 @@ __global__ void k_clear_flags(int32_t* flags, int64_t n_flags, int32_t* counter,
 // with predecessors)
 __global__ void k_seed_flags(int32_t* flags, int32_t* list, int32_t* counter,
                              const ProbDev* probs, const JobDev* jobs, int n_prob, int tx, int tz,
-                             int tree_phase, unsigned long long* key, unsigned long long* pmin) {
+                             int tree_phase, unsigned long long* key, unsigned long long* pmin,
+                             const int32_t* err) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_prob) return;
+  if (p >= n_prob || *err) return;  // bad class map: nothing runs
   const ProbDev pr = probs[p];
   if (tree_phase && pr.pred == nullptr) return;
   const JobDev jb = jobs[pr.job];
@@ -770,6 +804,7 @@ __global__ void __launch_bounds__(kRelaxThreads) k_tight_out(RelaxArgs a) {
   extern __shared__ double smem_d[];
   __shared__ int s_prob;
   const int T = blockIdx.x;
+  if (*a.err) return;  // bad class map: the fields were never initialised
   if (threadIdx.x == 0) {
     int lo = 0, hi = a.n_prob - 1;
     while (lo < hi) {
@@ -1123,7 +1158,7 @@ __device__ __forceinline__ void relax_tree(const RelaxArgs& a, int round, int T)
 // nodes.  blockIdx.y = problem.
 __global__ void k_pred(RelaxArgs a) {
   const ProbDev pr = a.probs[blockIdx.y];
-  if (!pr.pred) return;
+  if (!pr.pred || *a.err) return;
   const JobDev jb = a.jobs[pr.job];
   const int64_t n = (int64_t)jb.nx * jb.nz;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
@@ -1148,8 +1183,32 @@ __device__ __forceinline__ void visit(const RelaxArgs& a, int round, int T) {
   if constexpr (PH == 0) relax_tau<G>(a, round, T);
   else relax_tree(a, round, T);
 }
+// Caller's abort word, read through the system scope (pinned host memory).
+__device__ __forceinline__ bool host_abort(const RelaxArgs& a) {
+  return __hip_atomic_load(a.abort_host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
+}
+
+// Per-round launches with an abort word: workgroup 0 polls the word and
+// records it for the following rounds; every workgroup leaves once the
+// record is set.  True if this workgroup should leave now.
+__device__ __forceinline__ bool round_aborted(const RelaxArgs& a) {
+  if (!a.abort_host) return false;
+  __shared__ int s_ab;
+  if (threadIdx.x == 0) {
+    int ab = __hip_atomic_load(a.abort_seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!ab && blockIdx.x == 0 && host_abort(a)) {
+      __hip_atomic_store(a.abort_seen, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ab = 1;
+    }
+    s_ab = ab;
+  }
+  __syncthreads();
+  return s_ab != 0;
+}
+
 template <int G, int PH>
 __device__ __forceinline__ void round_tiles(const RelaxArgs& a, int round) {
+  if (round_aborted(a)) return;
   if (blockIdx.x == 0) reset_pmin(a, round);
   if ((int)gridDim.x == a.n_tiles) {
     visit<G, PH>(a, round, blockIdx.x);  // inactive tiles leave at once
@@ -1189,7 +1248,8 @@ constexpr uint64_t kBarrierWaitTicks = 200000000ull;  // 2 s of the 100 MHz real
 struct PersistArgs {
   int max_rounds;
   uint32_t* bar;    // [0] arrivals, [1] generation, [2] abort
-  int32_t* result;  // [phase]: rounds to convergence, -1 cap reached, -2 aborted
+  int32_t* result;  // [phase]: rounds to convergence, -1 cap reached, -2 barrier timed out,
+                    // -3 the caller's abort word was raised
 };
 
 // Device-wide barrier; false if aborted.  Release before arriving and
@@ -1243,8 +1303,17 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_persist(RelaxArgs a, Pe
       else relax_tree(a, round, T);
       __syncthreads();  // LDS is reused by the next tile
     }
+    // the caller's abort word, polled once per round by workgroup 0 and
+    // published by the barrier below, so every workgroup leaves together
+    if (a.abort_host && blockIdx.x == 0 && threadIdx.x == 0 && host_abort(a))
+      __hip_atomic_store(a.abort_seen, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (!grid_barrier(p)) {
       if (threadIdx.x == 0) p.result[PH] = -2;
+      return;
+    }
+    if (a.abort_host &&
+        __hip_atomic_load(a.abort_seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) p.result[PH] = -3;
       return;
     }
     if (__hip_atomic_load(&a.counter[round + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
@@ -1259,7 +1328,12 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_persist(RelaxArgs a, Pe
 // A phase run for a fixed number of per-round launches (graph capture):
 // rounds to convergence (the first round that activated nothing, + 1) or
 // -1 if the budget was too short.  One thread.
-__global__ void k_round_count(const int32_t* counter, int max_rounds, int32_t* result) {
+__global__ void k_round_count(const int32_t* counter, int max_rounds, int32_t* result,
+                              const int32_t* abort_seen) {
+  if (*abort_seen) {
+    *result = -3;
+    return;
+  }
   int r = -1;
   for (int q = 1; q <= max_rounds; ++q)
     if (counter[q] == 0) {
@@ -1270,9 +1344,9 @@ __global__ void k_round_count(const int32_t* counter, int max_rounds, int32_t* r
 }
 
 // unreachable nodes: t* = +inf.  blockIdx.y = problem.
-__global__ void k_tstar_finish(const ProbDev* probs, const JobDev* jobs) {
+__global__ void k_tstar_finish(const ProbDev* probs, const JobDev* jobs, const int32_t* err) {
   const ProbDev pr = probs[blockIdx.y];
-  if (!pr.tstar) return;
+  if (!pr.tstar || *err) return;
   const int64_t n = (int64_t)jobs[pr.job].nx * jobs[pr.job].nz;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * blockDim.x)
@@ -1454,7 +1528,8 @@ static int make_plan(const chert_trace_job* jobs, int n_jobs, const chert_trace_
 // 16, then 32, then 64 at a time (a converged phase's extra launches find
 // no active tile and leave at once; each check costs a stream drain).
 static int run_rounds(hipStream_t s, const RelaxArgs& a, void (*kern)(RelaxArgs, int),
-                      const char* name, int grid, size_t lds, int max_rounds, int* rounds) {
+                      const char* name, int grid, size_t lds, int max_rounds,
+                      const volatile int32_t* abort_flag, int* rounds) {
   constexpr int kMaxBatch = 64;
   int32_t counts[kMaxBatch];
   int batch = 16;
@@ -1464,10 +1539,19 @@ static int run_rounds(hipStream_t s, const RelaxArgs& a, void (*kern)(RelaxArgs,
     for (int q = 0; q < nb; ++q)
       CHERT_LAUNCH(name, kern, dim3((unsigned)grid), dim3((unsigned)tile_threads(a.tx, a.tz)), lds,
                    s, a, r + q);
+    int32_t seen = 0;
     hipError_t e = hipMemcpyAsync(counts, a.counter + r + 1, sizeof(int32_t) * nb,
                                   hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && abort_flag)
+      e = hipMemcpyAsync(&seen, a.abort_seen, sizeof(int32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+    // rounds the kernels skipped after seeing the word activate nothing, so
+    // the word is checked before the counts
+    if (abort_flag && (seen || *abort_flag)) {
+      *rounds = r + nb;
+      return fail(CHERT_ERR_ABORTED, "aborted by the caller");
+    }
     for (int q = 0; q < nb; ++q)
       if (counts[q] == 0) {
         *rounds = r + q + 1;
@@ -1659,6 +1743,18 @@ static int prepare(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
   a.pmin = (unsigned long long*)(ws + P.off_pmin);
   a.wmin = (const double*)(ws + P.off_wmin);
   a.bucket = o->bucket_width;
+  a.abort_seen = (int32_t*)(ws + P.off_err + 224);
+  a.abort_host = nullptr;
+  if (o->abort_flag_host) {
+    // only page-locked host memory the device can read is accepted
+    hipPointerAttribute_t at{};
+    const hipError_t pe = hipPointerGetAttributes(&at, (const void*)o->abort_flag_host);
+    if (pe != hipSuccess || at.type != hipMemoryTypeHost || !at.devicePointer) {
+      (void)hipGetLastError();
+      return fail(CHERT_ERR_INVALID_ARG, "abort_flag_host must be pinned host memory");
+    }
+    a.abort_host = (const int32_t*)at.devicePointer;
+  }
   Q->lds[0] = lds_bytes(P.lw, P.lh, P.w_lds_doubles, P.n_off, P.tx, P.tz);
   Q->lds[1] = tree_lds_bytes(P.lw, P.lh, P.nw, P.n_off, P.tx, P.tz);
   Q->pa.max_rounds = P.max_rounds;
@@ -1708,6 +1804,10 @@ static int enqueue(const Prepared& Q, const chert_trace_job* jobs, int n_jobs,
   const PersistArgs& pa = Q.pa;
   uint8_t* ws = Q.ws;
   const uint32_t outs = o->outputs;
+  CHERT_LAUNCH("k_trace_begin", k_trace_begin, dim3(1), dim3(64), 0, s, a.err, a.stats, pa.result,
+               a.abort_seen);
+  for (int j = 0; j < n_jobs; ++j)
+    if (!Q.jd[j].per_node) enqueue_class_check(Q.jd[j].class_id, P.nodes[j], Q.jd[j].K, a.err, s);
   for (int j = 0; j < n_jobs; ++j) {
     const chert_trace_job& J = jobs[j];
     chert_cache_layout lay;
@@ -1745,8 +1845,7 @@ static int enqueue(const Prepared& Q, const chert_trace_job* jobs, int n_jobs,
   for (int64_t n : P.nodes) max_nodes = n > max_nodes ? n : max_nodes;
   const unsigned gx = (unsigned)((max_nodes + 255) / 256 > 1024 ? 1024 : (max_nodes + 255) / 256);
   const dim3 pgrid(gx, (unsigned)P.n_prob);
-  CHERT_LAUNCH("k_init_fields", k_init_fields, pgrid, dim3(256), 0, s, Q.dprobs, Q.djobs, a.err,
-               a.stats, pa.result);
+  CHERT_LAUNCH("k_init_fields", k_init_fields, pgrid, dim3(256), 0, s, Q.dprobs, Q.djobs, a.err);
   const int64_t n_flags = 2 * P.n_tiles;
   auto init_flags = [&](int tree_phase) {
     CHERT_LAUNCH("k_clear_flags", k_clear_flags, dim3(256), dim3(256), 0, s, a.flags, n_flags,
@@ -1754,7 +1853,7 @@ static int enqueue(const Prepared& Q, const chert_trace_job* jobs, int n_jobs,
                  3 * P.n_prob);
     CHERT_LAUNCH("k_seed_flags", k_seed_flags, dim3((P.n_prob + 63) / 64), dim3(64), 0, s,
                  a.flags, a.list, a.counter, Q.dprobs, Q.djobs, P.n_prob, P.tx, P.tz,
-                 tree_phase, a.key, a.pmin);
+                 tree_phase, a.key, a.pmin, (const int32_t*)a.err);
   };
   const int G = o->push_group ? o->push_group : 2;
   static const char* kname[2] = {"k_relax_tau", "k_relax_tree"};
@@ -1773,12 +1872,12 @@ static int enqueue(const Prepared& Q, const chert_trace_job* jobs, int n_jobs,
         CHERT_LAUNCH(kname[ph], round_kernel(ph, G, Q.lean), dim3((unsigned)Q.rgrid[ph]),
                      dim3((unsigned)tile_threads(a.tx, a.tz)), lds, s, a, r);
       CHERT_LAUNCH("k_round_count", k_round_count, dim3(1), dim3(1), 0, s, a.counter,
-                   P.max_rounds, pa.result + ph);
+                   P.max_rounds, pa.result + ph, (const int32_t*)a.abort_seen);
       rounds[ph] = 0;
       return CHERT_OK;
     }
     return run_rounds(s, a, round_kernel(ph, G, Q.lean), kname[ph], Q.rgrid[ph], lds, P.max_rounds,
-                      &rounds[ph]);
+                      o->abort_flag_host, &rounds[ph]);
   };
   int rc = phase(0);
   if (rc) return rc;
@@ -1790,7 +1889,8 @@ static int enqueue(const Prepared& Q, const chert_trace_job* jobs, int n_jobs,
     if (rc) return rc;
     CHERT_LAUNCH("k_pred", k_pred, pgrid, dim3(256), 0, s, a);
     if (outs & CHERT_OUT_TSTAR)
-      CHERT_LAUNCH("k_tstar_finish", k_tstar_finish, pgrid, dim3(256), 0, s, Q.dprobs, Q.djobs);
+      CHERT_LAUNCH("k_tstar_finish", k_tstar_finish, pgrid, dim3(256), 0, s, Q.dprobs, Q.djobs,
+                   (const int32_t*)a.err);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
@@ -1819,6 +1919,8 @@ static int finish(const Prepared& Q, const chert_trace_opts* o, hipStream_t s, i
       rounds[ph] = ran[ph] ? hres[ph] : 0;
       if (ran[ph] && hres[ph] == -2 && !status)
         status = fail(CHERT_ERR_HIP, "persistent relaxation: device-wide barrier timed out");
+      if (ran[ph] && hres[ph] == -3 && !status)
+        status = fail(CHERT_ERR_ABORTED, "aborted by the caller");
       if (ran[ph] && hres[ph] == -1 && !status)
         status = fail(CHERT_ERR_NO_CONVERGENCE, "relaxation round cap reached");
       if (rounds[ph] < 0) rounds[ph] = Q.P.max_rounds;

@@ -317,3 +317,50 @@ def test_class_pair_table_index_limit():
     with pytest.raises(C.ChertError) as e:
         C.chert_trace_batch(b, opts, None, stream=0)
     assert e.value.code == 2
+
+
+def test_cache_desc_solver_fields_validated():
+    """resid_tol must be finite and >= 0, max_iter >= 0 and the reserved
+    word 0; each violation is INVALID_ARG before any device work."""
+    C.chert_cache_layout_of(C.cache_desc(resid_tol=1e-12, max_iter=3), 2)
+    for kw in ({"resid_tol": -1e-9}, {"resid_tol": float("nan")}, {"resid_tol": float("inf")},
+               {"max_iter": -1}):
+        with pytest.raises(C.ChertError) as e:
+            C.chert_cache_layout_of(C.cache_desc(**kw), 2)
+        assert e.value.code == 1
+    d = C.cache_desc()
+    d.reserved = 7
+    with pytest.raises(C.ChertError) as e:
+        C.chert_cache_layout_of(d, 2)
+    assert e.value.code == 1
+
+
+def test_abi_struct_layouts_match_header(tmp_path):
+    """Every structure the binding marshals has the size and field offsets
+    that a C compiler gives the declarations in include/chert.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"chert_class": C.ChertClass, "chert_cache_desc": C.CacheDesc,
+               "chert_cache_layout": C.CacheLayout, "chert_cache_stats": C.CacheStats,
+               "chert_grid": C.Grid, "chert_trace_job": C.TraceJob,
+               "chert_trace_stats": C.TraceStats, "chert_trace_opts": C.TraceOpts}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "chert.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "abi.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "abi"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    got = {(out[i], out[i + 1]): int(out[i + 2]) for i in range(0, len(out), 3)}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

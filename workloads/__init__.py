@@ -227,6 +227,28 @@ def complex_2d(nx=1701, nz=351, h=10.0, seed=None, n_layers=30, n_faults=5,
                         tuple(modes), radius)
 
 
+SHOT_GRIDS = ((401, 201), (801, 401), (1201, 301), (1701, 351))
+
+
+def config4(grids=SHOT_GRIDS, sources_per_grid=32):
+    """Batched shots: grids of uneven size at 10 m from the structurally
+    complex generator (200 m of water kept; layers and faults scaled to the
+    extent), each with its own seed, and sources_per_grid seafloor sources
+    at ix = round((j + 1/2) nx / S) on the first row below the water; qP and
+    qSV, radius 5."""
+    out = []
+    for g, (nx, nz) in enumerate(grids):
+        depth = (nz - 1) * 10.0
+        m = complex_2d(nx=nx, nz=nz, h=10.0, seed=seed_for(4) * 10 + g,
+                       n_layers=max(5, min(30, round(30 * depth / 3500.0))),
+                       n_faults=max(1, round(5 * nx / 1701)), modes=(QP, QSV), radius=5)
+        iz = 20  # first row below the water
+        m.sources = [int(round((j + 0.5) * nx / sources_per_grid)) + nx * iz
+                     for j in range(sources_per_grid)]
+        out.append(m)
+    return out
+
+
 def surrogate_training_rows(n, seed=None):
     """Thomsen rows [n, 10] (vp0, vs0, rho, eps, delta, gamma, tilt,
     azimuth, qp, qs) spanning the media of the layered and the structurally
