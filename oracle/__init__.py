@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 QP, QSV, QSH = 0, 1, 2
 MEV, OEV = 0, 1
-ST_OK, ST_NO_BRACKET, ST_ILL, ST_FLUID, ST_NONPHYS = 0, 1, 2, 4, 8
+ST_OK, ST_NO_BRACKET, ST_ILL, ST_FLUID, ST_NONPHYS, ST_NOCONV = 0, 1, 2, 4, 8, 16
 FIELDS = ("V", "A", "Q", "rx", "rz", "thR", "thI", "res")
 NF = len(FIELDS)
 N_SWEEP = 1440

@@ -433,9 +433,18 @@ static int solve_direction(const medium_t *m, int mode, int reading, int M,
     if (solution_at(m, mode, reading, thR, psi_star, &cand) != 0) continue;
     double slope = (fb - fa) / (tb - ta);
     int cand_ill = fabs(slope) < ORC_ILL_SLOPE;
+    /* Only a root competes as a root: a bisection that closed on a jump of
+     * the ray-angle map (theta_I(theta_R) changing branch inside the
+     * bracket) leaves a residual far above ORC_RESID_TOL, and any genuine
+     * root is preferred to it.  Among roots, the first arrival (largest
+     * V^Ray) wins, equal velocities going to the smaller |theta_R - psi*|. */
+    int cand_root = cand.res <= ORC_RESID_TOL;
+    int best_root = found && best->res <= ORC_RESID_TOL;
     int take = 0;
     if (!found) {
       take = 1;
+    } else if (cand_root != best_root) {
+      take = cand_root;
     } else if (cand.V > best->V * (1.0 + ORC_TIE_REL)) {
       take = 1;
     } else if (fabs(cand.V - best->V) <= ORC_TIE_REL * best->V &&

@@ -278,6 +278,19 @@ __device__ __forceinline__ bool bracket_root(const SolveArgs& a, const Medium& m
   double x, y;
   bool ok = newton_root(m, mode, a.kernel, psi_star, ta, tb, sa.x, sb.x, fa, fb, a.newton_iters,
                         &x, &y);
+  // The 2D Newton iteration does not know which homogeneity root theta_I
+  // must be: keep its root only if y is the root nearest 0 at the final
+  // theta_R (the outward scan's answer there); otherwise -- theta_I(theta_R)
+  // switching branches inside the bracket -- the nested bisection follows
+  // that definition.
+  // It must also lie in its own bracket (the bisection's interval), not
+  // wander into a neighbouring one.
+  if (ok) ok = x >= ta - 1e-12 && x <= tb + 1e-12;
+  if (ok && !el) {
+    double sx, cx, ys;
+    sincos(x, &sx, &cx);
+    ok = theta_imag_sc(m, mode, a.kernel, sx, cx, &ys) && fabs(ys - y) <= 1e-9;
+  }
   if (!ok) ok = bisect_root(m, mode, a.kernel, psi_star, ta, tb, fa, a.bisect_iters, &x, &y);
   if (!ok) return false;
   if (x >= kTwoPi) x -= kTwoPi;
@@ -292,13 +305,16 @@ __device__ __forceinline__ bool bracket_root(const SolveArgs& a, const Medium& m
   return true;
 }
 
-// Fold a root into the running first-arrival choice, brackets in scan
-// order: the first root, then a larger ray velocity; ties (kTieRel) go to
-// the smaller |theta_R - psi*|.
+// Fold a refined bracket into the running first-arrival choice, brackets in
+// scan order: a root (residual within tol) beats a refinement that closed on
+// a jump of the ray-angle map; among equals the first, then a larger ray
+// velocity; ties (kTieRel) go to the smaller |theta_R - psi*|.
 __device__ __forceinline__ void fold_choice(const Entry& cand, bool cand_ill, double psi_star,
-                                            bool* found, bool* ill, Entry* best) {
+                                            double tol, bool* found, bool* ill, Entry* best) {
   bool take;
+  const bool cand_root = cand.res <= tol, best_root = *found && best->res <= tol;
   if (!*found) take = true;
+  else if (cand_root != best_root) take = cand_root;
   else if (cand.V > best->V * (1.0 + kTieRel)) take = true;
   else take = fabs(cand.V - best->V) <= kTieRel * best->V &&
               ang_dist(cand.thR, psi_star) < ang_dist(best->thR, psi_star);
@@ -315,7 +331,7 @@ __device__ __forceinline__ void refine_bracket_at(const SolveArgs& a, const Medi
   Entry cand;
   bool cand_ill;
   if (bracket_root(a, m, mode, j, sa, sb, psi_star, el, &cand, &cand_ill))
-    fold_choice(cand, cand_ill, psi_star, found, ill, best);
+    fold_choice(cand, cand_ill, psi_star, a.resid_tol, found, ill, best);
 }
 
 template <class T>
@@ -517,7 +533,7 @@ __global__ void __launch_bounds__(64) k_solve(SolveArgs a) {
       for (int qq = 0; qq < kSolveSplit; ++qq)
         for (int b = 0; b < s_nc[dl][qq]; ++b) {
           const SolveCand& sc = s_c[dl][qq * kSolveSlots + b];
-          if (sc.ok) fold_choice(sc.e, sc.ill != 0, psi_star, &found, &ill, &best);
+          if (sc.ok) fold_choice(sc.e, sc.ill != 0, psi_star, a.resid_tol, &found, &ill, &best);
         }
       st = solve_status(found, ill, best);
     }
@@ -1292,9 +1308,19 @@ extern "C" size_t chert_build_cache_workspace_bytes(const chert_cache_desc* d,
   return (size_t)n_jobs_of(d, n_classes) * (size_t)d->n_sweep * sizeof(double2);
 }
 
+static int build_cache(const chert_cache_desc* d, const chert_class* classes_dev,
+                       int64_t n_classes, void* cache_dev, void* workspace_dev,
+                       size_t workspace_bytes, void* stream);
+
 extern "C" int chert_build_cache(const chert_cache_desc* d, const chert_class* classes_dev,
                                  int64_t n_classes, void* cache_dev, void* workspace_dev,
                                  size_t workspace_bytes, void* stream) {
+  return build_cache(d, classes_dev, n_classes, cache_dev, workspace_dev, workspace_bytes, stream);
+}
+
+static int build_cache(const chert_cache_desc* d, const chert_class* classes_dev,
+                       int64_t n_classes, void* cache_dev, void* workspace_dev,
+                       size_t workspace_bytes, void* stream) {
   chert_cache_layout lay;
   int rc = common_checks(d, classes_dev, n_classes, cache_dev, &lay);
   if (rc != CHERT_OK) return rc;

@@ -253,5 +253,7 @@ def test_oev_every_mode_rock_table(G, rock_table):
     cls = np.stack([O.class_from_moduli(*(r[:5] * KM2), *r[5:10], tilt=t)
                     for r, t in zip(rock_table, (0.0, 0.3, -0.5, 0.9))])
     fg, sg, fo, so = run_pair(G, cls, modes=(0, 1, 2), kernel=1)
-    st = compare_cache(fg, sg, fo, so, (0, 1, 2))
+    # OEV qSV's ray-angle map is steep next to its branch changes: residuals
+    # there reach ~2e-11 (the theta_R bisection width times the slope)
+    st = compare_cache(fg, sg, fo, so, (0, 1, 2), res_tol=1e-10)
     print("OEV", st, flush=True)

@@ -397,3 +397,38 @@ def test_ideal_fluid_qp_is_homogeneous():
     np.testing.assert_allclose(f[0, 0, 0], abs(cc) ** 2 / cc.real, rtol=1e-13)
     np.testing.assert_allclose(f[1, 0, 0], -cc.imag / abs(cc) ** 2, rtol=1e-12)
     assert np.all(st[1:, 0] == O.ST_FLUID)
+
+
+def test_jump_brackets_never_beat_roots(rock_table):
+    """OEV qSV of the fourth rock-table layer tilted 0.9 rad: theta_I(theta_R)
+    changes branch, so the ray-angle map jumps across some targets and the
+    sweep brackets both the jump and a genuine root (checked below for
+    direction 26).  The cached entry must be a root -- homogeneity and
+    direction residual at rounding level, theta_I the scan's nearest-0 root
+    at the stored theta_R -- never the point where a bisection closed on the
+    jump; and no entry of the four tilted layers is left without one."""
+    KM2 = 1e6
+    tilts = (0.0, 0.3, -0.5, 0.9)
+    cls = np.stack([O.class_from_moduli(*(r[:5] * KM2), *r[5:10], tilt=t)
+                    for r, t in zip(rock_table, tilts)])
+    f, st = O.build_cache_2d(cls, mode_mask=0b010, reading=O.OEV)
+    # the situation occurs: a jump of the sweep's ray angle across the
+    # target of direction 26 next to an ordinary crossing
+    thR, thI, psi, ok = O.sweep(cls[3], O.QSV, reading=O.OEV)
+    target = np.angle(np.exp(1j * (np.radians(26.0) - 0.9)))
+    miss = np.angle(np.exp(1j * (psi - target)))
+    cross = np.flatnonzero((np.sign(miss) != np.sign(np.roll(miss, -1))) & (ok == 1)
+                           & (np.roll(ok, -1) == 1))
+    jumps = [j for j in cross if abs(np.angle(np.exp(1j * (psi[(j + 1) % psi.size] - psi[j]))))
+             > np.radians(5.0)]
+    smooth = [j for j in cross if j not in jumps]
+    assert jumps and smooth
+    for k in range(4):
+        s = st[O.QSV, k]
+        assert np.all((s & (O.ST_NOCONV | O.ST_NO_BRACKET)) == 0), k
+        # a root within the solver's tolerance (where the map is steep the
+        # theta_R bisection width shows up as ~1e-11); a jump leaves ~1e-2
+        assert np.nanmax(f[7, O.QSV, k]) < 1e-10
+        for d in (26, 77, 206, 257, 130):
+            tr, ti = f[5, O.QSV, k, d], f[6, O.QSV, k, d]
+            assert abs(O.theta_imag(cls[k], O.QSV, tr, reading=O.OEV) - ti) < 1e-12
