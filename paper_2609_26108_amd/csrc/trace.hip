@@ -622,16 +622,36 @@ __device__ __forceinline__ void relax_tau(const RelaxArgs& a, int round, int T) 
       const int kj = s.cls[j];
       const int64_t gj = gnode(a, c, jb, j);
       double best = s.val[j];
+      if (jb.per_node) {
+        // the group's eight consecutive entries of row j, loaded together
+        const double* row = jb.W + ((int64_t)pr.field * jb.nx * jb.nz + gj) * n_off;
+        double wv[kPullGroup];
 #pragma unroll
-      for (int u = 0; u < kPullGroup; ++u) {
-        const int o = g * kPullGroup + u;
-        if (o >= n_off) break;
-        const int ii = j - s.off[o];
-        const int ki = s.cls[ii];
-        if (ki < 0) continue;
-        const double cand =
-            __dadd_rn(s.val[ii], w_pull(jb, Wp, pr.field, ki & kClassMask, kj, o, n_off, gj));
-        if (cand < best) best = cand;
+        for (int u = 0; u < kPullGroup; ++u) {
+          const int o = g * kPullGroup + u;
+          wv[u] = o < n_off ? row[o] : INFINITY;
+        }
+#pragma unroll
+        for (int u = 0; u < kPullGroup; ++u) {
+          const int o = g * kPullGroup + u;
+          if (o >= n_off) break;
+          const int ii = j - s.off[o];
+          if (s.cls[ii] < 0) continue;
+          const double cand = __dadd_rn(s.val[ii], wv[u]);
+          if (cand < best) best = cand;
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < kPullGroup; ++u) {
+          const int o = g * kPullGroup + u;
+          if (o >= n_off) break;
+          const int ii = j - s.off[o];
+          const int ki = s.cls[ii];
+          if (ki < 0) continue;
+          const double cand =
+              __dadd_rn(s.val[ii], w_pull(jb, Wp, pr.field, ki & kClassMask, kj, o, n_off, gj));
+          if (cand < best) best = cand;
+        }
       }
       if (best < s.val[j]) atomicMin((unsigned long long*)&s.val[j], dbits(best));
     }
@@ -862,6 +882,31 @@ __global__ void __launch_bounds__(kRelaxThreads) k_tight_out(RelaxArgs a) {
   const bool ok = ki >= 0 && ti < INFINITY;
   const int64_t gi = gnode(a, c, jb, ml);
   const int64_t gn = (int64_t)jb.nx * jb.nz;
+  if (jb.per_node) {
+    // row i holds the edge i -> i + o at entry n_off - 1 - o: eight
+    // consecutive entries (64 B) are loaded together, then tested
+    const double* row = jb.W + ((int64_t)pr.field * gn + gi) * n_off;
+    for (int w = 0; w < nw; ++w) {
+      uint32_t m = 0u;
+      for (int b0 = 0; b0 < 32 && w * 32 + b0 < n_off; b0 += 8) {
+        const int o0 = w * 32 + b0;
+        double wv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          wv[u] = (ok && o0 + u < n_off) ? row[n_off - 1 - (o0 + u)] : INFINITY;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int o = o0 + u;
+          if (o >= n_off) break;
+          const int j = ml + off[o];
+          const double tj = val[j];
+          if (cls[j] >= 0 && tj < INFINITY && __dadd_rn(ti, wv[u]) == tj) m |= 1u << (b0 + u);
+        }
+      }
+      pr.tight[(int64_t)w * gn + gi] = m;
+    }
+    return;
+  }
   for (int w = 0; w < nw; ++w) {
     uint32_t m = 0u;
     for (int b = 0; ok && b < 32; ++b) {
