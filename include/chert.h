@@ -211,6 +211,24 @@ int chert_build_cache(const chert_cache_desc *d, const chert_class *classes_dev,
                       int64_t n_classes, void *cache_dev, void *workspace_dev,
                       size_t workspace_bytes, void *stream);
 
+/* chert_build_cache for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with the theta_R sweep tables
+ * in a file-scope device array of chert_build_cache_noalloc_max_bytes()
+ * (16 MiB) instead of a caller's workspace.  The call allocates nothing and
+ * enqueues kernels only (no memset, no host copy), asynchronously on
+ * `stream`.  Each GPU holds its own copy of the array until the process
+ * ends; its device address is resolved on the first call on that device.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (concurrent streams, or host threads) race and must be serialised by
+ * the caller.  Nothing in the array needs to start at zero: each call
+ * writes every sweep entry before reading it.  CAPACITY when the build's
+ * sweep tables (chert_build_cache_workspace_bytes) exceed the array; other
+ * errors as chert_build_cache. */
+size_t chert_build_cache_noalloc_max_bytes(void);
+int chert_build_cache_noalloc(const chert_cache_desc *d, const chert_class *classes_dev,
+                              int64_t n_classes, void *cache_dev, void *stream);
+
 /* ------------------------------------------------------------------------
  * Stage 2: traveltime fields (eqs 22, 24, 27-34; Algorithm 2, tracing).
  * Graph: every node connects to the nodes at the forward-star offsets o with

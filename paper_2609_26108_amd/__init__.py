@@ -43,7 +43,7 @@ EXPORTS = (
     "chert_build_cache_surrogate_workspace_bytes", "chert_build_cache_surrogate",
     "chert_trace_graph_create", "chert_trace_graph_launch", "chert_trace_graph_finish",
     "chert_trace_graph_destroy", "chert_trace_autotune_workspace_bytes", "chert_trace_autotune",
-    "chert_star_3d",
+    "chert_star_3d", "chert_build_cache_noalloc", "chert_build_cache_noalloc_max_bytes",
 )
 WARM_NSTATS = 10
 # parameter blocks of the surrogate, in their order in the parameter vector
@@ -172,6 +172,9 @@ def lib():
         L.chert_build_cache_workspace_bytes.argtypes = [P, i64]
         L.chert_build_cache_workspace_bytes.restype = sz
         L.chert_build_cache.argtypes = [P, P, i64, P, P, sz, P]
+        L.chert_build_cache_noalloc.argtypes = [P, P, i64, P, P]
+        L.chert_build_cache_noalloc_max_bytes.argtypes = []
+        L.chert_build_cache_noalloc_max_bytes.restype = sz
         L.chert_trace_workspace_bytes.argtypes = [P, i64, P, i32, P]
         L.chert_trace_workspace_bytes.restype = sz
         L.chert_trace_field.argtypes = [P, P, i64, P, i32, P, i32, P, P, P, P, P, P, P, sz, P]
@@ -354,6 +357,17 @@ def chert_build_cache(desc, classes_dev, n_classes, cache_dev, workspace_dev, st
     ws = workspace_dev.numel() * workspace_dev.element_size() if workspace_dev is not None else 0
     _check(lib().chert_build_cache(ctypes.byref(desc), _ptr(classes_dev), n_classes,
                                    _ptr(cache_dev), _ptr(workspace_dev), ws, _stream(stream)))
+
+
+def chert_build_cache_noalloc(desc, classes_dev, n_classes, cache_dev, stream=None):
+    """chert_build_cache with its scratch in the library's own device array
+    (no workspace, no allocation); see include/chert.h."""
+    _check(lib().chert_build_cache_noalloc(ctypes.byref(desc), _ptr(classes_dev), n_classes,
+                                           _ptr(cache_dev), _stream(stream)))
+
+
+def chert_build_cache_noalloc_max_bytes():
+    return int(lib().chert_build_cache_noalloc_max_bytes())
 
 
 def make_grid(nx, nz, hx, hz, radius, class_id_dev):

@@ -20,6 +20,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "chert.h"
 #include "chert_internal.h"
 #include "mlp.h"
@@ -1316,6 +1318,61 @@ extern "C" int chert_build_cache(const chert_cache_desc* d, const chert_class* c
                                  int64_t n_classes, void* cache_dev, void* workspace_dev,
                                  size_t workspace_bytes, void* stream) {
   return build_cache(d, classes_dev, n_classes, cache_dev, workspace_dev, workspace_bytes, stream);
+}
+
+// ---------------------------------------------------- allocation-free build
+// Scratch of chert_build_cache_noalloc: the theta_R sweep tables live in this
+// file-scope device array (one copy per GPU, held until the process ends).
+// Host code never passes the array's name to a kernel: it is a host-side
+// stand-in; the device address comes from hipGetSymbolAddress, once per
+// device.
+constexpr size_t kNoAllocScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+// Device address of this device's scratch array (resolved on first use).
+static int scratch_of_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CHERT_ERR_UNSUPPORTED, "device index too large");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return fail(CHERT_ERR_HIP, e != hipSuccess ? hipGetErrorString(e)
+                                                 : "no device address for the build scratch");
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return CHERT_OK;
+}
+
+extern "C" size_t chert_build_cache_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+extern "C" int chert_build_cache_noalloc(const chert_cache_desc* d,
+                                         const chert_class* classes_dev, int64_t n_classes,
+                                         void* cache_dev, void* stream) {
+  chert_cache_layout lay;
+  int rc = common_checks(d, classes_dev, n_classes, cache_dev, &lay);
+  if (rc != CHERT_OK) return rc;
+  const size_t need = chert_build_cache_workspace_bytes(d, n_classes);
+  if (need > kNoAllocScratchBytes)
+    return fail(CHERT_ERR_CAPACITY,
+                "sweep tables exceed the 16 MiB build scratch (use chert_build_cache)");
+  void* ws = nullptr;
+  if (need > 0) {
+    rc = scratch_of_current_device(&ws);
+    if (rc != CHERT_OK) return rc;
+  }
+  return build_cache(d, classes_dev, n_classes, cache_dev, ws, need > 0 ? kNoAllocScratchBytes : 0,
+                     stream);
 }
 
 static int build_cache(const chert_cache_desc* d, const chert_class* classes_dev,
