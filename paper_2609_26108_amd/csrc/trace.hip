@@ -90,6 +90,41 @@ __device__ __forceinline__ double w_push(const JobDev& jb, const double* Wp, int
   return Wp[(ki * jb.K + kj) * n_off + o];
 }
 
+// Per-node weights of offsets g*G .. g*G+G-1 read from row `row` of a
+// table whose rows hold the edge i -> i + o at entry n_off - 1 - o (the push
+// side: row i).  The block is contiguous and, since a 2D star's size is a
+// multiple of 8 and rows start 64-byte aligned, 16-byte aligned: it is read
+// with 16-byte loads.  w[u] = weight of offset g*G + u.
+template <int G>
+__device__ __forceinline__ void row_block_rev(const double* W, int64_t row, int n_off, int g,
+                                              double* w) {
+  const double* p = W + row * n_off + (n_off - (g + 1) * G);
+  if constexpr (G == 1) {
+    w[0] = p[0];
+  } else {
+#pragma unroll
+    for (int q = 0; q < G / 2; ++q) {
+      const double2 v = reinterpret_cast<const double2*>(p)[q];
+      w[G - 1 - 2 * q] = v.x;
+      w[G - 2 - 2 * q] = v.y;
+    }
+  }
+}
+
+// The same for the pull side (row j holds the edge j - o -> j at entry o):
+// w[u] = weight of offset g*G + u.
+template <int G>
+__device__ __forceinline__ void row_block(const double* W, int64_t row, int n_off, int g,
+                                          double* w) {
+  const double2* p = reinterpret_cast<const double2*>(W + row * n_off + g * G);
+#pragma unroll
+  for (int q = 0; q < G / 2; ++q) {
+    const double2 v = p[q];
+    w[2 * q] = v.x;
+    w[2 * q + 1] = v.y;
+  }
+}
+
 struct ProbDev {
   double* tau;     // [n_nodes] this problem's field
   unsigned long long* key;  // [n_nodes] hop << 32 | predecessor offset index
@@ -623,14 +658,10 @@ __device__ __forceinline__ void relax_tau(const RelaxArgs& a, int round, int T) 
       const int64_t gj = gnode(a, c, jb, j);
       double best = s.val[j];
       if (jb.per_node) {
-        // the group's eight consecutive entries of row j, loaded together
-        const double* row = jb.W + ((int64_t)pr.field * jb.nx * jb.nz + gj) * n_off;
+        // the group's eight consecutive entries of row j (|O| is a multiple
+        // of 8, so the group is whole)
         double wv[kPullGroup];
-#pragma unroll
-        for (int u = 0; u < kPullGroup; ++u) {
-          const int o = g * kPullGroup + u;
-          wv[u] = o < n_off ? row[o] : INFINITY;
-        }
+        row_block<kPullGroup>(jb.W, (int64_t)pr.field * jb.nx * jb.nz + gj, n_off, g, wv);
 #pragma unroll
         for (int u = 0; u < kPullGroup; ++u) {
           const int o = g * kPullGroup + u;
@@ -725,10 +756,13 @@ __device__ __forceinline__ void relax_tau(const RelaxArgs& a, int round, int T) 
       }
       return;
     }
-    // per-node weights from HBM: the G loads go out together
+    // per-node weights from HBM: the group's G entries of row i in 16-byte
+    // loads, issued before any atomic
     int jv[G];
     double cv[G];
     bool tv[G];
+    double wv[G];
+    if (live) row_block_rev<G>(jb.W, (int64_t)pr.field * jb.nx * jb.nz + gi, n_off, g, wv);
 #pragma unroll
     for (int u = 0; u < G; ++u) {
       const int o = g * G + u;
@@ -739,7 +773,7 @@ __device__ __forceinline__ void relax_tau(const RelaxArgs& a, int round, int T) 
         const int j = i + offs[u];
         const int kj = s.cls[j];
         if (kj >= 0 && !(kj & kHaloBit)) {
-          const double cand = __dadd_rn(vi, w_push(jb, Wp, pr.field, ki, kj, o, n_off, gi));
+          const double cand = __dadd_rn(vi, wv[u]);
           jv[u] = j;
           cv[u] = cand;
           tv[u] = cand < s.val[j];
@@ -885,15 +919,17 @@ __global__ void __launch_bounds__(kRelaxThreads) k_tight_out(RelaxArgs a) {
   if (jb.per_node) {
     // row i holds the edge i -> i + o at entry n_off - 1 - o: eight
     // consecutive entries (64 B) are loaded together, then tested
-    const double* row = jb.W + ((int64_t)pr.field * gn + gi) * n_off;
     for (int w = 0; w < nw; ++w) {
       uint32_t m = 0u;
       for (int b0 = 0; b0 < 32 && w * 32 + b0 < n_off; b0 += 8) {
         const int o0 = w * 32 + b0;
         double wv[8];
+        if (ok) {
+          row_block_rev<8>(jb.W, (int64_t)pr.field * gn + gi, n_off, o0 / 8, wv);
+        } else {
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          wv[u] = (ok && o0 + u < n_off) ? row[n_off - 1 - (o0 + u)] : INFINITY;
+          for (int u = 0; u < 8; ++u) wv[u] = INFINITY;
+        }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int o = o0 + u;
@@ -1499,6 +1535,9 @@ static int make_plan(const chert_trace_job* jobs, int n_jobs, const chert_trace_
   if (P->tx < P->R || P->tz < P->R || P->tx * P->tz > kRelaxThreads)
     return fail(CHERT_ERR_INVALID_ARG, "tile must be >= radius per side and <= 1024 nodes");
   P->n_off = star_2d(P->R, 1.0, 1.0, 4, nullptr, nullptr, nullptr, nullptr);
+  // the star is symmetric under the square's eight symmetries, so |O| is a
+  // multiple of 8; the per-node kernels read whole 8-offset groups
+  if (P->n_off % 8) return fail(CHERT_ERR_UNSUPPORTED, "forward star size not a multiple of 8");
   P->nw = (P->n_off + 31) / 32;
   P->lw = P->tx + 2 * P->R;
   P->lh = P->tz + 2 * P->R;
