@@ -324,7 +324,8 @@ typedef struct chert_trace_opts {
   int32_t tile_x;     /* relaxation tile width in nodes (0 = default 32)   */
   int32_t tile_z;     /* relaxation tile height in nodes (0 = default 32)  */
   int32_t max_rounds; /* cap on relaxation rounds per phase (0 = default)  */
-  int32_t push_group; /* star offsets per push work item: 1, 2 or 4 (0 = 2) */
+  int32_t push_group; /* star offsets per push work item: 1, 2, 4, or 8 on
+                         2D tiles (0 = 2)                                  */
   int32_t launch;     /* CHERT_LAUNCH_PER_ROUND (0), _PERSISTENT (1) or
                          _FRONTIER (2)                                     */
   double bucket_width;/* ordering width in units of the batch's smallest
@@ -408,7 +409,7 @@ int chert_trace_batch(const chert_trace_job *jobs, int32_t n_jobs,
  * with bucket widths 0 (one bucket), 4, 16, 32, 64, 128, 256 (units of the
  * smallest edge weight) and the 3D tiles 8x8x8, 8x8x16, 16x16x4, 4x4x16
  * with push groups 1, 2, 4; in 2D the frontier with widths 16 and 64 and the
- * tiles 32x32, 64x16, 16x64, 32x16, 16x32, 128x8, 16x16 with push groups 1, 2, 4,
+ * tiles 32x32, 64x16, 16x64, 32x16, 16x32, 128x8, 16x16 with push groups 1, 2, 4, 8,
  * per-round and persistent launch, then, if tiles win, their ordering width
  * 16, 64 or 256 on the fastest shape.  Each is timed (HIP events,
  * second of two runs) on a probe batch made of the first source of every

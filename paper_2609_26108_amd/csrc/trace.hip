@@ -1502,8 +1502,9 @@ int validate_job_2d(const chert_trace_job& j, uint32_t outs) {
 
 static int validate_opts(const chert_trace_opts* o) {
   if (!o) return fail(CHERT_ERR_INVALID_ARG, "null options");
-  if (o->push_group != 0 && o->push_group != 1 && o->push_group != 2 && o->push_group != 4)
-    return fail(CHERT_ERR_INVALID_ARG, "push_group must be 0, 1, 2 or 4");
+  if (o->push_group != 0 && o->push_group != 1 && o->push_group != 2 && o->push_group != 4 &&
+      o->push_group != 8)
+    return fail(CHERT_ERR_INVALID_ARG, "push_group must be 0, 1, 2, 4 or 8");
   if (o->launch != CHERT_LAUNCH_PER_ROUND && o->launch != CHERT_LAUNCH_PERSISTENT)
     return fail(CHERT_ERR_INVALID_ARG, "launch must be CHERT_LAUNCH_PER_ROUND or _PERSISTENT");
   if (!(o->bucket_width >= 0.0) || !isfinite(o->bucket_width))
@@ -1651,15 +1652,20 @@ typedef void (*PersistKern)(RelaxArgs, PersistArgs);
 
 static RoundKern round_kernel(int ph, int G, bool lean) {
   if (ph == 0) {
-    if (lean) return G == 1 ? k_relax_tau<1, 1> : (G == 2 ? k_relax_tau<2, 1> : k_relax_tau<4, 1>);
-    return G == 1 ? k_relax_tau<1, 0> : (G == 2 ? k_relax_tau<2, 0> : k_relax_tau<4, 0>);
+    if (lean)
+      return G == 1 ? k_relax_tau<1, 1>
+                    : (G == 2 ? k_relax_tau<2, 1> : (G == 4 ? k_relax_tau<4, 1> : k_relax_tau<8, 1>));
+    return G == 1 ? k_relax_tau<1, 0>
+                  : (G == 2 ? k_relax_tau<2, 0> : (G == 4 ? k_relax_tau<4, 0> : k_relax_tau<8, 0>));
   }
   return lean ? k_relax_tree<1> : k_relax_tree<0>;  // one lane per frontier node: no push groups
 }
 
 static PersistKern persist_kernel(int ph, int G) {
   if (ph == 0)
-    return G == 1 ? k_relax_persist<1, 0> : (G == 2 ? k_relax_persist<2, 0> : k_relax_persist<4, 0>);
+    return G == 1 ? k_relax_persist<1, 0>
+                  : (G == 2 ? k_relax_persist<2, 0>
+                            : (G == 4 ? k_relax_persist<4, 0> : k_relax_persist<8, 0>));
   return k_relax_persist<1, 1>;  // tree phase: no push groups
 }
 
@@ -2111,7 +2117,8 @@ extern "C" int chert_trace_field(const chert_cache_desc* d, const void* cache_de
 namespace {
 const int kTuneTiles[][2] = {{32, 32}, {64, 16}, {16, 64}, {32, 16}, {16, 32}, {128, 8}, {16, 16}};
 const int kTuneTiles3D[][2] = {{8, 8}, {8, 16}, {16, 4}, {4, 16}};
-const int kTuneGroups[] = {1, 2, 4};
+const int kTuneGroups[] = {1, 2, 4};        // 3D tiles
+const int kTuneGroups2D[] = {1, 2, 4, 8};   // 2D tiles
 const int kTuneLaunch[] = {CHERT_LAUNCH_PER_ROUND, CHERT_LAUNCH_PERSISTENT};
 }  // namespace
 
@@ -2185,7 +2192,7 @@ extern "C" int chert_trace_autotune(const chert_trace_job* jobs, int32_t n_jobs,
       }
   if (!three_d)
     for (const auto& t : kTuneTiles)
-      for (int G : kTuneGroups)
+      for (int G : kTuneGroups2D)
         for (int L : kTuneLaunch) {
           chert_trace_opts c = *o;
           c.tile_x = t[0];

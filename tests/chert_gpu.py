@@ -47,12 +47,13 @@ def import_cache(fields_np, status_np, desc, K):
 
 
 def trace(cache, desc, K, nx, nz, hx, hz, radius, class_id_np, mode, sources,
-          outputs=C.OUT_ALL, tile_x=0, tile_z=0, launch=0, bucket_width=0.0):
+          outputs=C.OUT_ALL, tile_x=0, tile_z=0, launch=0, bucket_width=0.0, push_group=0):
     cid = None  # one class per node
     if class_id_np is not None:
         cid = torch.from_numpy(np.ascontiguousarray(class_id_np, dtype=np.int32).reshape(-1)).to(DEV)
     g = C.make_grid(nx, nz, hx, hz, radius, cid)
-    o = C.trace_opts(outputs, tile_x, tile_z, launch=launch, bucket_width=bucket_width)
+    o = C.trace_opts(outputs, tile_x, tile_z, launch=launch, bucket_width=bucket_width,
+                     push_group=push_group)
     n = nx * nz
     S = len(sources)
     out = {

@@ -52,7 +52,7 @@ def assert_fields_equal(g, o, s_idx=0):
 
 
 def imported_case(G, model, modes, tile=(0, 0), sources=None, n_sweep=1440, launch=0,
-                  bucket=0.0):
+                  bucket=0.0, group=0):
     cls, f, s = oracle_cache(model, modes, n_sweep)
     Cm = C()
     desc = Cm.cache_desc(n_dirs=model.n_dirs, modes=modes, n_sweep=n_sweep)
@@ -62,7 +62,7 @@ def imported_case(G, model, modes, tile=(0, 0), sources=None, n_sweep=1440, laun
     for mode in modes:
         g = G.trace(cache, desc, K, model.nx, model.nz, model.hx, model.hz, model.radius,
                     model.class_id, mode, sources, tile_x=tile[0], tile_z=tile[1],
-                    launch=launch, bucket_width=bucket)
+                    launch=launch, bucket_width=bucket, push_group=group)
         for si, src in enumerate(sources):
             o = O.trace_2d(model.nx, model.nz, model.hx, model.hz, model.class_id,
                            model.radius, f[0, mode], f[1, mode], s[mode], src)
@@ -87,6 +87,14 @@ def test_tile_shapes_give_identical_fields(G, tile, bucket):
     reaches the same bits."""
     m = W.small_layered(nx=53, nz=29, radius=4, seed=3)
     imported_case(G, m, (1,), tile=tile, bucket=bucket)
+
+
+@pytest.mark.parametrize("group,launch", [(1, 0), (4, 1), (8, 0), (8, 1)])
+def test_push_groups_give_identical_fields(G, group, launch):
+    """Every push-group width (offsets per push work item), per-round and
+    persistent, on class caches, reaches the oracle's bits."""
+    m = W.small_layered(nx=47, nz=31, radius=5, seed=8)
+    imported_case(G, m, (0, 1), tile=(16, 16), group=group, launch=launch)
 
 
 def test_multiple_sources_one_call(G):
@@ -318,7 +326,7 @@ def test_autotuned_options_give_identical_fields(G):
     if opts.launch == Cm.LAUNCH_FRONTIER:
         assert opts.bucket_width in (16.0, 64.0)
     else:
-        assert opts.push_group in (1, 2, 4) and opts.tile_x * opts.tile_z <= 1024
+        assert opts.push_group in (1, 2, 4, 8) and opts.tile_x * opts.tile_z <= 1024
         assert opts.bucket_width in (0.0, 16.0, 64.0, 256.0)
     for j in jobs:
         for t in j[5].values():
@@ -328,8 +336,10 @@ def test_autotuned_options_give_identical_fields(G):
     check_batch(jobs)
 
 
-@pytest.mark.parametrize("launch,bucket", [(0, 0.0), (0, 8.0), (1, 32.0), (2, 0.0), (2, 16.0)])
-def test_per_node_trace_bitwise(G, launch, bucket):
+@pytest.mark.parametrize("launch,bucket,group", [(0, 0.0, 0), (0, 8.0, 0), (1, 32.0, 0),
+                                                 (2, 0.0, 0), (2, 16.0, 0), (0, 0.0, 8),
+                                                 (1, 0.0, 4), (0, 0.0, 1)])
+def test_per_node_trace_bitwise(G, launch, bucket, group):
     """Per-node cache (no class map): GPU traveltimes and predecessors on an
     imported oracle cache are bitwise the oracle's, on the tiles and on the
     node frontier."""
@@ -352,7 +362,7 @@ def test_per_node_trace_bitwise(G, launch, bucket):
                    pred_p=torch.empty((1, n), dtype=torch.int32, device=G.DEV),
                    pred_a=torch.empty((1, n), dtype=torch.int32, device=G.DEV))
         grid = Cm.make_grid(m.nx, m.nz, m.hx, m.hz, m.radius, None)
-        opts = Cm.trace_opts(Cm.OUT_ALL, launch=launch, bucket_width=bucket)
+        opts = Cm.trace_opts(Cm.OUT_ALL, launch=launch, bucket_width=bucket, push_group=group)
         ws = torch.empty(Cm.chert_trace_workspace_bytes(desc, N, grid, 1, opts),
                          dtype=torch.uint8, device=G.DEV)
         Cm.chert_trace_field(desc, cache, N, grid, mode, m.sources, opts, workspace_dev=ws, **out)
