@@ -422,3 +422,59 @@ def test_lean_builds_per_node_many_sources_bitwise(G):
         o = O.trace_2d(m.nx, m.nz, m.hx, m.hz, None, m.radius, f[0, 0], f[1, 0], s[0], src,
                        subset=sub)
         assert_fields_equal(g, o, si)
+
+
+def test_list_mode_bitwise(G):
+    """A batch with more tiles than four times the resident workgroups (64
+    sources x 2 fields x 20 tiles of 32 x 32 = 2560): the per-round launches
+    walk each round's list of active tiles instead of one workgroup per
+    tile.  Eager and as a replayed graph, every field, t* and predecessor
+    equals the oracle's bitwise."""
+    Cm = C()
+    m = W.small_layered(nx=160, nz=128, radius=3, seed=31)
+    cls, f, s = oracle_cache(m, (0,), n_sweep=720)
+    K = cls.shape[0]
+    desc = Cm.cache_desc(n_dirs=360, modes=(0,), n_sweep=720)
+    cache = G.import_cache(f, s, desc, K)
+    rng = np.random.default_rng(77)
+    srcs = sorted(rng.choice(m.n_nodes, 64, replace=False).tolist())
+    cid = torch.from_numpy(m.class_id.reshape(-1).astype(np.int32)).to(G.DEV)
+    grid = Cm.make_grid(m.nx, m.nz, m.hx, m.hz, m.radius, cid)
+    n, S = m.n_nodes, len(srcs)
+    out = {k: torch.empty((S, n), dtype=torch.float64, device=G.DEV)
+           for k in ("tau_r", "tau_i", "tstar")}
+    out.update({k: torch.empty((S, n), dtype=torch.int32, device=G.DEV)
+                for k in ("pred_p", "pred_a")})
+    b = Cm.Batch()
+    b.add(desc, cache, K, grid, 0, srcs, **out)
+    st = Cm.TraceStats()
+    opts = Cm.trace_opts(Cm.OUT_ALL, 32, 32, stats=st)
+    ws = torch.empty(Cm.chert_trace_batch_workspace_bytes(b, opts), dtype=torch.uint8,
+                     device=G.DEV)
+    Cm.chert_trace_batch(b, opts, ws)
+    torch.cuda.synchronize()
+    print(st.as_dict(), flush=True)
+    eager = {k: v.clone() for k, v in out.items()}
+    gopts = Cm.trace_opts(Cm.OUT_ALL, 32, 32, max_rounds=max(st.rounds) + 8)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        graph = Cm.TraceGraph(b, gopts, ws, stream=stream)
+    try:
+        for rep in range(2):
+            for t in out.values():
+                t.fill_(-4)
+            torch.cuda.synchronize()
+            graph.launch(stream)
+            graph.finish(None, stream)
+            torch.cuda.synchronize()
+            for k, v in out.items():
+                assert torch.equal(v, eager[k]), (rep, k)
+    finally:
+        graph.close()
+    g = {"tauR": eager["tau_r"].cpu().numpy(), "tauI": eager["tau_i"].cpu().numpy(),
+         "tstar": eager["tstar"].cpu().numpy(), "predP": eager["pred_p"].cpu().numpy(),
+         "predA": eager["pred_a"].cpu().numpy()}
+    for si in range(0, S, 7):
+        o = O.trace_2d(m.nx, m.nz, m.hx, m.hz, m.class_id, m.radius, f[0, 0], f[1, 0], s[0],
+                       srcs[si])
+        assert_fields_equal(g, o, si)
