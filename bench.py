@@ -122,13 +122,14 @@ def parse():
                    help="complex2d, shots: trace with the default (or given) launch options")
     p.add_argument("--bucket", type=float, default=0.0,
                    help="node-frontier near/far bucket width (units of the smallest weight)")
-    p.add_argument("--workload", choices=("shots", "layered", "complex2d", "3d"),
+    p.add_argument("--workload", choices=("shots", "layered", "complex2d", "3d", "ablation"),
                    default="shots",
                    help="shots: 128 shots over 4 uneven per-node grids, surrogate-started "
                         "caches + one batched trace per step (default, the headline line); "
                         "layered: the 5-layer model on class caches; "
                         "complex2d: per-node caches of the structurally complex model, "
-                        "plain vs surrogate-started; 3d: the 3D layered model")
+                        "plain vs surrogate-started; 3d: the 3D layered model; ablation: "
+                        "angular step and star radius against the finest setting")
     p.add_argument("--plain-stride", type=int, default=64,
                    help="complex2d: time the plain per-node build on every n-th node")
     p.add_argument("--full-plain", action="store_true",
@@ -179,6 +180,9 @@ def main():
         return
     if args.workload == "3d":
         run_3d(args)
+        return
+    if args.workload == "ablation":
+        run_ablation(args)
         return
     m = W.config2()
     K = len(m.layers)
@@ -978,6 +982,140 @@ def cpu_baseline_shots(grids, solves_total, node_fields_total, shots, opts):
                                  "cache_V_rel_max": float(relV.max()) if relV.size else 0.0,
                                  "fields_bitwise": bitwise},
             "cpu_count": os.cpu_count()}
+
+
+ABL_STEPS = (720, 360, 180, 36)   # 0.5, 1, 2 and 10 degree angular sampling
+ABL_RADII = (2, 3, 4, 5, 6)
+
+
+def _misfit(a, ref):
+    """RMS and max of tau - tau_ref over nodes reachable in both [s], and the
+    max relative difference."""
+    fin = torch_isfinite(a) & torch_isfinite(ref)
+    d = (a[fin] - ref[fin])
+    rel = d.abs() / ref[fin].abs().clamp_min(1e-300)
+    return {"rms_ms": 1e3 * float(d.pow(2).mean().sqrt().item()),
+            "max_abs_ms": 1e3 * float(d.abs().max().item()),
+            "max_rel": float(rel.max().item()),
+            "reachable": int(fin.sum().item())}
+
+
+def torch_isfinite(t):
+    import torch
+    return torch.isfinite(t)
+
+
+def run_ablation(args):
+    """Angular-step and star-radius ablations (the paper's angular-sampling
+    and node-density study): angular steps 0.5, 1, 2 and 10 degrees and
+    forward-star radii 2..6, on the layered model (class caches, qP/qSV/qSH)
+    and on the structurally complex model (per-node surrogate-started caches
+    on the star's bins, qSV).  For every setting: cache build and trace
+    times, and the tau_R misfit against the finest setting (0.5 degree,
+    radius 6)."""
+    import torch
+    import paper_2609_26108_amd as C
+    import workloads as W
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    res = {"metric": METRIC, "workload": "ablation", "n_gpus": 1, "dtype": "f64",
+           "data": "synthetic (seeded workloads.config2, workloads.complex_2d)",
+           "config": {"workload": "angular step {0.5, 1, 2, 10} deg x star radius {2..6}; "
+                                  "layered 401x201 @5 m (class caches) and complex 1701x351 "
+                                  "@10 m (per-node caches)", "steps_deg": [360 / n for n in ABL_STEPS],
+                      "radii": list(ABL_RADII), "reference": "0.5 deg, radius 6"}}
+    # layered model, class caches: one cache per step, one trace per radius
+    m = W.config2()
+    K = len(m.layers)
+    cls = torch.from_numpy(np.stack([C.chert_class_from_thomsen(*L.thomsen_args()).as_array()
+                                     for L in m.layers])).to(dev)
+    cid = torch.from_numpy(m.class_id.reshape(-1).astype(np.int32)).to(dev)
+    n = m.n_nodes
+    taus, lay2 = {}, {}
+    for nd in ABL_STEPS:
+        desc = C.cache_desc(n_dirs=nd, modes=m.modes)
+        lay = C.chert_cache_layout_of(desc, K)
+        cache = torch.zeros(lay.total_bytes, dtype=torch.uint8, device=dev)
+        ws = torch.empty(max(C.chert_build_cache_workspace_bytes(desc, K), 1), dtype=torch.uint8,
+                         device=dev)
+        C.chert_build_cache(desc, cls, K, cache, ws, stream=stream)  # warm-up
+        ev = _events(torch, stream)
+        C.chert_build_cache(desc, cls, K, cache, ws, stream=stream)
+        t_build = _elapsed(torch, ev, stream)
+        for R in ABL_RADII:
+            grid = C.make_grid(m.nx, m.nz, m.hx, m.hz, R, cid)
+            b = C.Batch()
+            outs = {}
+            for mode in m.modes:
+                outs[mode] = torch.empty((1, n), dtype=torch.float64, device=dev)
+                b.add(desc, cache, K, grid, mode, m.sources, tau_r=outs[mode])
+            o = C.trace_opts(C.OUT_TAU_R)
+            tws = torch.empty(C.chert_trace_batch_workspace_bytes(b, o), dtype=torch.uint8,
+                              device=dev)
+            C.chert_trace_batch(b, o, tws, stream=stream)
+            ev = _events(torch, stream)
+            C.chert_trace_batch(b, o, tws, stream=stream)
+            t_trace = _elapsed(torch, ev, stream)
+            taus[(nd, R)] = {mode: outs[mode][0].clone() for mode in m.modes}
+            lay2[(nd, R)] = {"build_s": t_build, "trace_s": t_trace}
+    ref = taus[(720, 6)]
+    res["layered"] = {f"{360 / nd:g}deg_R{R}": {
+        **lay2[(nd, R)],
+        "misfit": {str(mode): _misfit(taus[(nd, R)][mode], ref[mode]) for mode in m.modes}}
+        for nd in ABL_STEPS for R in ABL_RADII}
+    del taus
+
+    # structurally complex model, per-node caches (surrogate-started)
+    blob, tinfo = train_surrogate(args, dev, stream)
+    res["training"] = tinfo
+    mc = W.complex_2d()
+    rows = mc.param_rows()
+    nn = rows.shape[0]
+    ccls = torch.empty((nn, 13), dtype=torch.float64, device=dev)
+    C.chert_classes_from_thomsen(torch.from_numpy(rows).to(dev), ccls)
+    mode = mc.modes[0]
+    taus, out = {}, {}
+    for nd in ABL_STEPS:
+        for R in ABL_RADII:
+            sub = C.star_subset(R, mc.hx, mc.hz, nd)
+            desc = C.cache_desc(n_dirs=nd, modes=(mode,), subset=sub)
+            lay = C.chert_cache_layout_of(desc, nn)
+            cache = torch.zeros(lay.total_bytes, dtype=torch.uint8, device=dev)
+            wws = torch.empty(C.chert_build_cache_surrogate_workspace_bytes(desc, nn),
+                              dtype=torch.uint8, device=dev)
+            wst = torch.zeros(C.WARM_NSTATS, dtype=torch.int64, device=dev)
+            ev = _events(torch, stream)
+            C.chert_build_cache_surrogate(desc, ccls, nn, blob, cache, wws, wst, stream=stream)
+            t_build = _elapsed(torch, ev, stream)
+            del wws
+            grid = C.make_grid(mc.nx, mc.nz, mc.hx, mc.hz, R, None)
+            tr = torch.empty((1, nn), dtype=torch.float64, device=dev)
+            o = C.trace_opts(C.OUT_TAU_R)
+            tws = torch.empty(C.chert_trace_workspace_bytes(desc, nn, grid, 1, o),
+                              dtype=torch.uint8, device=dev)
+            C.chert_trace_field(desc, cache, nn, grid, mode, mc.sources, o, tr, None, None, None,
+                                None, tws, stream=stream)
+            ev = _events(torch, stream)
+            C.chert_trace_field(desc, cache, nn, grid, mode, mc.sources, o, tr, None, None, None,
+                                None, tws, stream=stream)
+            t_trace = _elapsed(torch, ev, stream)
+            del tws, cache
+            taus[(nd, R)] = tr[0].clone()
+            w = dict(zip(C.WARM_STATS, wst.cpu().numpy().tolist()))
+            out[(nd, R)] = {"columns": int(len(sub)), "build_s": t_build, "trace_s": t_trace,
+                            "fallback_jobs": w["fallback_jobs"]}
+    ref = taus[(720, 6)]
+    res["complex"] = {f"{360 / nd:g}deg_R{R}": {**out[(nd, R)],
+                                                "misfit": _misfit(taus[(nd, R)], ref)}
+                      for nd in ABL_STEPS for R in ABL_RADII}
+    # the paper's cost statement: the 1-degree cache costs about half the
+    # 0.5-degree one (class caches: the number of solved directions)
+    res["layered_build_ratio_1deg_over_0p5deg"] = (res["layered"]["1deg_R5"]["build_s"] /
+                                                   res["layered"]["0.5deg_R5"]["build_s"])
+    res["value"] = res["complex"]["1deg_R5"]["misfit"]["rms_ms"]
+    res["unit"] = "ms RMS tau_R misfit of the 1-degree, radius-5 per-node trace against 0.5 deg / R 6"
+    res["higher_is_better"] = False
+    print(json.dumps(res))
 
 
 def useful_edges_3d(nx, ny, nz, ox, oy, oz):
