@@ -84,8 +84,9 @@ enum {
 typedef struct chert_cache_stats {
   int64_t n_entries;    /* stored entries of the built modes                */
   int64_t n_converged;  /* status OK or ILL only: a root within resid_tol   */
-  int64_t n_fallback;   /* entries of jobs the surrogate-started build sent
-                           back to the full plain solver (0 for plain)      */
+  int64_t n_fallback;   /* entries the surrogate-started build sent back
+                           to the plain solver: whole 2D jobs, single 3D
+                           directions (0 for plain builds)                  */
   int64_t n_noconv;     /* CHERT_ST_NOCONV set                               */
   int64_t n_illcond;    /* CHERT_ST_ILL set                                  */
   int64_t n_nobracket;  /* CHERT_ST_NO_BRACKET set                           */
@@ -596,7 +597,14 @@ size_t chert_build_cache_surrogate_workspace_bytes(const chert_cache_desc *d,
  *      failed check in 4, is solved again by the full plain path, so each
  *      entry equals the plain solver's to the Newton tolerance.
  * stats_dev: nullable device int64[CHERT_WARM_NSTATS], overwritten.
- * UNSUPPORTED above 512 stored directions (n_dirs or n_subset). */
+ * UNSUPPORTED above 512 stored directions (n_dirs or n_subset) in 2D.
+ * 3D caches (dim 3): every (mode, class, Fibonacci direction) is polished
+ * on its own from its prediction under the checks of step 3 (the fold test
+ * against the elastic map of its class); a direction near a fold or failing
+ * a check is solved by the plain sweep-and-bracket search from its (mode,
+ * class) sweep table, so again each entry equals the plain solver's.  The
+ * counters then hold [0] (mode, class) jobs, [1] directions sent to the
+ * plain search, [2]..[7] as in 2D; [8], [9] stay 0. */
 int chert_build_cache_surrogate(const chert_cache_desc *d,
                                 const chert_class *classes_dev,
                                 int64_t n_classes, const void *blob_dev,

@@ -1116,6 +1116,168 @@ __global__ void __launch_bounds__(64) k_warm_fold(WarmArgs w) {
   }
 }
 
+// ------------------------------------------------------- 3D warm start
+// Surrogate-started 3D caches: every (mode, class, Fibonacci direction) is
+// polished on its own from its prediction (one lane each) under the same
+// acceptance checks as in 2D; directions near a fold of the elastic map, or
+// failing a check, are solved by the plain sweep-and-bracket search from
+// their (mode, class) sweep table.  Jobs are (mode, class) pairs.
+struct Warm3Args {
+  SolveArgs so;                 // dim 3: n_solve = n_cols = n_dirs
+  const void* blob;
+  float2* pred;                 // [jobs][n_dirs] (theta_R - psi, theta_I)
+  uint32_t* fold;               // [jobs][kFoldWords] fold bins of the elastic map
+  int32_t* fb_list;             // job * n_dirs + direction, for the plain search
+  int32_t* fb_len;
+  unsigned long long* stats;    // CHERT_WARM_NSTATS counters
+  double resid_tol;
+};
+
+// target polar angle of direction s to the class's symmetry axis (eq 35)
+__device__ __forceinline__ double warm3_target(const SolveArgs& a, int s, const chert_class& c) {
+  return polar_to_axis(fib_dir(a, s), c);
+}
+
+__global__ void __launch_bounds__(mlp::kThreads) k_warm3_predict(Warm3Args w, int64_t n_rows) {
+  __shared__ mlp::InferTile t;
+  const SolveArgs& a = w.so;
+  const mlp::Net n = mlp::net_of(w.blob);
+  const int64_t base = (int64_t)blockIdx.x * mlp::kInferRows;
+  for (int r = threadIdx.x; r < mlp::kInferRows; r += blockDim.x) {
+    const int64_t e = base + r;
+    float f[mlp::kIn] = {};
+    if (e < n_rows) {
+      const int64_t job = e / a.n_solve;
+      const int s = (int)(e % a.n_solve);
+      const chert_class c = a.classes[job % a.n_classes];
+      mlp::features(c, a.modes[job / a.n_classes], warm3_target(a, s, c), f);
+    }
+    mlp::stage_row(n, t.x, r, f, e >= n_rows);
+  }
+  __syncthreads();
+  mlp::forward_infer(n, t, [&](int r, int col, float v) {
+    if (col < 2 && base + r < n_rows) (&w.pred[base + r].x)[col] = v;
+  });
+}
+
+// fold bins of each job's elastic ray-angle map (all bins if the map is not
+// finite everywhere); one wavefront per job
+__global__ void __launch_bounds__(64) k_warm3_folds(Warm3Args w) {
+  __shared__ double s_psi[kProxyN];
+  __shared__ uint32_t s_fold[kFoldWords];
+  __shared__ int s_all;
+  const SolveArgs& a = w.so;
+  const int64_t job = blockIdx.x;
+  const chert_class c = a.classes[job % a.n_classes];
+  const int mode = a.modes[job / a.n_classes];
+  if (threadIdx.x < kFoldWords) s_fold[threadIdx.x] = 0u;
+  if (threadIdx.x == 0) s_all = 0;
+  __syncthreads();
+  if (!class_block(c, mode)) proxy_folds(elastic_of(load_medium(c)), mode, a.kernel, s_psi, s_fold,
+                                         &s_all);
+  __syncthreads();
+  if (threadIdx.x < kFoldWords)
+    w.fold[job * kFoldWords + threadIdx.x] = s_all ? ~0u : s_fold[threadIdx.x];
+  if (threadIdx.x == 0) atomicAdd(&w.stats[0], 1ull);
+}
+
+// one lane per (job, direction): Newton polish from the prediction and the
+// checks of k_warm_solve; the rest go to the plain-search list
+__global__ void __launch_bounds__(64) k_warm3_solve(Warm3Args w, int64_t n_rows) {
+  const SolveArgs& a = w.so;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long cnt[CHERT_WARM_NSTATS] = {};
+  if (e < n_rows) {
+    const int64_t job = e / a.n_solve;
+    const int s = (int)(e % a.n_solve);
+    const int64_t k = job % a.n_classes;
+    const int mode = a.modes[job / a.n_classes];
+    const chert_class c = a.classes[k];
+    const int64_t idx = ((int64_t)mode * a.n_classes + k) * a.n_cols + s;
+    const int64_t stride = 3 * a.n_classes * (int64_t)a.n_cols;
+    const double3 f = fib_dir(a, s);
+    const int32_t blocked = class_block(c, mode);
+    cnt[2] = 1;
+    bool plain = false;
+    if (blocked) {
+      Entry none{};
+      none.V = NAN;
+      store_single(a, idx, stride, none, f, blocked);
+    } else {
+      const Medium m = load_medium(c);
+      const bool el = theta_i_zero(m, mode);
+      const double psi_star = polar_to_axis(f, c);
+      const int fb = fold_bin(psi_star);
+      double x, y, slope;
+      const float2 p = w.pred[e];
+      if ((w.fold[job * kFoldWords + (fb >> 5)] >> (fb & 31)) & 1u) {
+        cnt[3] = 1;
+        plain = true;
+      } else if (!warm_newton(m, mode, a.kernel, el, psi_star, psi_star + (double)p.x,
+                              (double)p.y, &x, &y, &slope)) {
+        cnt[4] = 1;
+        plain = true;
+      } else if (!(slope >= kWarmSlope)) {
+        cnt[5] = 1;
+        plain = true;
+      } else if (!el && !thi_is_nearest(m, mode, a.kernel, x, y)) {
+        cnt[6] = 1;
+        plain = true;
+      } else {
+        x = fmod(x, kTwoPi);
+        if (x < 0.0) x += kTwoPi;
+        const Vel v = energy_velocity(m, mode, a.kernel, x, y);
+        Entry en;
+        ray_quantities(v, &en);
+        en.thR = x;
+        en.thI = y;
+        const double h = el ? 0.0 : homog_residual(v);
+        en.res = fmax(fabs(h), fabs(wrap_pi(ray_angle(v) - psi_star)));
+        if (!(en.res <= w.resid_tol) || !(en.V > 0.0) || !isfinite(en.V) || !(en.A >= 0.0)) {
+          cnt[7] = 1;
+          plain = true;
+        } else {
+          store_single(a, idx, stride, en, f, CHERT_ST_OK);
+        }
+      }
+      if (plain) {
+        cnt[1] = 1;
+        w.fb_list[atomicAdd(w.fb_len, 1)] = (int32_t)e;
+      }
+    }
+  }
+  for (int q = 1; q < 8; ++q) {
+    unsigned long long v = cnt[q];
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    if (__lane_id() == 0 && v) atomicAdd(&w.stats[q], v);
+  }
+}
+
+// the plain sweep-and-bracket search for the listed directions, one lane
+// each, from the job's sweep table (read through the caches); grid-strided
+__global__ void __launch_bounds__(64) k_warm3_plain(Warm3Args w) {
+  __shared__ int s_br[64 * kMaxBr];
+  const SolveArgs& a = w.so;
+  const int n = *w.fb_len;
+  for (int64_t q0 = (int64_t)blockIdx.x * blockDim.x; q0 < n; q0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = q0 + threadIdx.x;
+    if (q >= n) continue;
+    const int64_t e = w.fb_list[q];
+    const int64_t job = e / a.n_solve;
+    const int s = (int)(e % a.n_solve);
+    const int64_t k = job % a.n_classes;
+    const int mode = a.modes[job / a.n_classes];
+    const chert_class c = a.classes[k];
+    const Medium m = load_medium(c);
+    const double3 f = fib_dir(a, s);
+    Entry best{};
+    const int32_t st = solve_dir(a, m, mode, FullTable{a.table + job * a.n_sweep, a.n_sweep},
+                                 polar_to_axis(f, c), s_br + threadIdx.x * kMaxBr, &best);
+    store_single(a, ((int64_t)mode * a.n_classes + k) * a.n_cols + s,
+                 3 * a.n_classes * (int64_t)a.n_cols, best, f, st);
+  }
+}
+
 __global__ void k_warm_zero(int32_t* fb_len, int32_t* win_len, unsigned long long* stats) {
   if (threadIdx.x == 0) *fb_len = 0;
   if (threadIdx.x == 1) *win_len = 0;
@@ -1162,10 +1324,11 @@ __device__ __forceinline__ unsigned long long wave_max(unsigned long long v) {
 
 // Counters of a built cache (chert_cache_stats) from its status and residual
 // arrays, over the modes of the mask; fb_len (nullable) is the number of
-// jobs the surrogate-started build re-solved with the plain solver.
+// items the surrogate-started build re-solved with the plain solver, each
+// holding fb_entries stored entries (a 2D job, or one 3D direction).
 __global__ void __launch_bounds__(256) k_cache_stats(const int32_t* status, const double* res,
                                                      int64_t per_mode, uint32_t mask,
-                                                     const int32_t* fb_len, int64_t cols_per_job,
+                                                     const int32_t* fb_len, int64_t fb_entries,
                                                      chert_cache_stats* st) {
   long long n = 0, conv = 0, noconv = 0, ill = 0, nob = 0, unus = 0;
   unsigned long long mr = 0ull;  // non-negative doubles order as their bits
@@ -1207,13 +1370,13 @@ __global__ void __launch_bounds__(256) k_cache_stats(const int32_t* status, cons
     atomicMax((unsigned long long*)&st->max_resid, mr);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0)
-    st->n_fallback = fb_len ? (int64_t)*fb_len * cols_per_job : 0;
+    st->n_fallback = fb_len ? (int64_t)*fb_len * fb_entries : 0;
 }
 
 // Enqueue the counters of a build into d->stats_dev (if set).
 static void enqueue_cache_stats(const chert_cache_desc* d, int64_t n_classes, uint8_t* cache,
                                 const chert_cache_layout& lay, const int32_t* fb_len,
-                                hipStream_t s) {
+                                int64_t fb_entries, hipStream_t s) {
   if (!d->stats_dev) return;
   const int n_cols = d->n_subset ? d->n_subset : d->n_dirs;
   const int64_t per_mode = n_classes * (int64_t)n_cols;
@@ -1223,7 +1386,7 @@ static void enqueue_cache_stats(const chert_cache_desc* d, int64_t n_classes, ui
   if (blocks > 2048) blocks = 2048;
   CHERT_LAUNCH("k_cache_stats_zero", k_cache_stats_zero, dim3(1), dim3(64), 0, s, d->stats_dev);
   CHERT_LAUNCH("k_cache_stats", k_cache_stats, dim3((unsigned)blocks), dim3(256), 0, s, status,
-               res, per_mode, d->mode_mask, fb_len, (int64_t)n_cols, d->stats_dev);
+               res, per_mode, d->mode_mask, fb_len, fb_entries, d->stats_dev);
 }
 
 }  // namespace chert
@@ -1420,7 +1583,7 @@ static int build_cache(const chert_cache_desc* d, const chert_class* classes_dev
       CHERT_LAUNCH("k_solve", k_solve<1>, dim3((unsigned)(jobs * chunks)), dim3(64),
                    (size_t)d->n_sweep * sizeof(double2), s, so);
   }
-  enqueue_cache_stats(d, n_classes, cache, lay, nullptr, s);
+  enqueue_cache_stats(d, n_classes, cache, lay, nullptr, 0, s);
   return launch_status();
 }
 
@@ -1428,10 +1591,20 @@ static int build_cache(const chert_cache_desc* d, const chert_class* classes_dev
 // fold-window job lists, their lengths and the internal counters
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// workspace of the 3D surrogate-started build: sweep tables, predictions,
+// fold bins, the plain-search list, its length and the counters
+static size_t warm3_bytes(const chert_cache_desc* d, int64_t n_classes) {
+  const size_t jobs = (size_t)n_jobs_of(d, n_classes);
+  const size_t rows = jobs * (size_t)d->n_dirs;
+  return al256(jobs * d->n_sweep * sizeof(double2)) + al256(rows * sizeof(float2)) +
+         al256(jobs * kFoldWords * sizeof(uint32_t)) + al256(rows * sizeof(int32_t)) + 256;
+}
+
 extern "C" size_t chert_build_cache_surrogate_workspace_bytes(const chert_cache_desc* d,
                                                               int64_t n_classes) {
   chert_cache_layout lay;
   if (!d || n_classes <= 0 || chert_cache_layout_of(d, n_classes, &lay) != CHERT_OK) return 0;
+  if (d->dim == 3) return warm3_bytes(d, n_classes);
   const SolveArgs so = solve_args(d, nullptr, n_classes, nullptr, lay, nullptr);
   const size_t jobs = (size_t)n_jobs_of(d, n_classes);
   return al256(jobs * so.n_solve * sizeof(float2)) + 2 * al256(jobs * sizeof(int32_t)) + 256 +
@@ -1447,8 +1620,6 @@ extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
   chert_cache_layout lay;
   int rc = common_checks(d, classes_dev, n_classes, cache_dev, &lay);
   if (rc != CHERT_OK) return rc;
-  if (d->dim == 3)
-    return fail(CHERT_ERR_UNSUPPORTED, "surrogate-started builds are 2D (3D: chert_build_cache)");
   if (!blob_dev || ((uintptr_t)blob_dev & 255u))
     return fail(CHERT_ERR_INVALID_ARG, "null or unaligned surrogate blob");
   if (!(resid_tol >= 0.0)) return fail(CHERT_ERR_INVALID_ARG, "negative residual tolerance");
@@ -1457,6 +1628,53 @@ extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
     return fail(CHERT_ERR_INVALID_ARG, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
   uint8_t* cache = (uint8_t*)cache_dev;
+  if (d->dim == 3) {
+    const int64_t jobs = n_jobs_of(d, n_classes);
+    const int64_t rows = jobs * (int64_t)d->n_dirs;
+    if (rows > 0x7fffffffLL) return fail(CHERT_ERR_INVALID_ARG, "too many entries");
+    uint8_t* ws = (uint8_t*)workspace_dev;
+    Warm3Args w{};
+    double2* table = (double2*)ws;
+    ws += al256((size_t)jobs * d->n_sweep * sizeof(double2));
+    w.so = solve_args(d, classes_dev, n_classes, cache, lay, table);
+    w.blob = blob_dev;
+    w.pred = (float2*)ws;
+    ws += al256((size_t)rows * sizeof(float2));
+    w.fold = (uint32_t*)ws;
+    ws += al256((size_t)jobs * kFoldWords * sizeof(uint32_t));
+    w.fb_list = (int32_t*)ws;
+    ws += al256((size_t)rows * sizeof(int32_t));
+    w.fb_len = (int32_t*)ws;
+    w.stats = stats_dev ? (unsigned long long*)stats_dev : (unsigned long long*)(ws + 64);
+    w.resid_tol = resid_tol > 0.0 ? resid_tol : 1e-11;
+    CHERT_LAUNCH("k_write_header", k_write_header, dim3(1), dim3(64), 0, s, cache, d->dim,
+                 d->n_dirs, d->mode_mask, d->kernel, d->n_sweep, d->n_subset, n_classes);
+    CHERT_LAUNCH("k_warm_zero", k_warm_zero, dim3(1), dim3(64), 0, s, w.fb_len, w.fb_len + 1,
+                 w.stats);
+    if (rows > 0) {
+      SweepArgs sa{};
+      sa.classes = classes_dev;
+      sa.n_classes = n_classes;
+      sa.n_modes = w.so.n_modes;
+      for (int i = 0; i < 3; ++i) sa.modes[i] = w.so.modes[i];
+      sa.kernel = d->kernel;
+      sa.n_sweep = d->n_sweep;
+      sa.table = table;
+      const int64_t total = jobs * d->n_sweep;
+      const int64_t sb = (total + 255) / 256 > 65536 ? 65536 : (total + 255) / 256;
+      CHERT_LAUNCH("k_sweep", k_sweep, dim3((unsigned)sb), dim3(256), 0, s, sa);
+      CHERT_LAUNCH("k_warm3_folds", k_warm3_folds, dim3((unsigned)jobs), dim3(64), 0, s, w);
+      CHERT_LAUNCH("k_warm3_predict", k_warm3_predict,
+                   dim3((unsigned)((rows + mlp::kInferRows - 1) / mlp::kInferRows)),
+                   dim3(mlp::kThreads), 0, s, w, rows);
+      CHERT_LAUNCH("k_warm3_solve", k_warm3_solve, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0,
+                   s, w, rows);
+      const int64_t pg = (rows + 63) / 64 < 8192 ? (rows + 63) / 64 : 8192;
+      CHERT_LAUNCH("k_warm3_plain", k_warm3_plain, dim3((unsigned)pg), dim3(64), 0, s, w);
+    }
+    enqueue_cache_stats(d, n_classes, cache, lay, w.fb_len, 1, s);  // listed: directions
+    return launch_status();
+  }
   WarmArgs w{};
   w.so = solve_args(d, classes_dev, n_classes, cache, lay, nullptr);
   if (w.so.n_solve > kMaxSubset / 2)
@@ -1502,6 +1720,6 @@ extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
                  (size_t)d->n_sweep * sizeof(double2), s, w.so, (const int32_t*)w.fb_list,
                  (const int32_t*)w.fb_len, jobs);
   }
-  enqueue_cache_stats(d, n_classes, cache, lay, w.fb_len, s);
+  enqueue_cache_stats(d, n_classes, cache, lay, w.fb_len, w.so.n_cols, s);  // listed: jobs
   return launch_status();
 }

@@ -436,3 +436,75 @@ def test_full_size_per_node_build_sampled(G, trained):
     cls_o = np.stack([O.class_from_thomsen(*r) for r in rows[pick]])
     fo, so = O.build_cache_2d(cls_o, mode_mask=0b010, subset=sub)
     compare_cache(fg, sg, fo, so, (1,))
+
+
+def _config5_classes(G, n=None):
+    C = _C()
+    m = W.config5(nx=8, ny=8, nz=8)
+    rows = np.stack([[L.vp0, L.vs0, L.rho, L.eps, L.delta, L.gamma, L.tilt, L.azimuth, L.qp, L.qs]
+                     for L in m.layers])
+    K = rows.shape[0]
+    classes = torch.empty((K, 13), dtype=torch.float64, device=G.DEV)
+    C.chert_classes_from_thomsen(torch.from_numpy(rows).to(G.DEV), classes)
+    return classes, K
+
+
+def warm_build_3d(G, classes, desc, blob, K):
+    C = _C()
+    lay = C.chert_cache_layout_of(desc, K)
+    cache = torch.zeros(lay.total_bytes, dtype=torch.uint8, device=G.DEV)
+    ws = torch.empty(C.chert_build_cache_surrogate_workspace_bytes(desc, K), dtype=torch.uint8,
+                     device=G.DEV)
+    stats = torch.zeros(C.WARM_NSTATS, dtype=torch.int64, device=G.DEV)
+    C.chert_build_cache_surrogate(desc, classes, K, blob, cache, ws, stats)
+    torch.cuda.synchronize()
+    return cache, dict(zip(C.WARM_STATS, stats.cpu().numpy().tolist()))
+
+
+def test_warm_3d_full_direction_set_matches_plain(G, trained):
+    """The surrogate-started 3D cache of the layered 3D model's six classes
+    on all 41,253 Fibonacci directions (qP, qSV): every entry has the plain
+    3D build's status and fields within 1e-10, most directions accepted from
+    the Newton polish; sampled entries also against the oracle's solve at
+    the direction's polar angle to the axis."""
+    C = _C()
+    blob, _ = trained
+    classes, K = _config5_classes(G)
+    N = O.N_FIB
+    desc = C.cache_desc(dim=3, n_dirs=N, modes=(0, 1))
+    plain = G.build_cache(classes, desc)
+    warm, st = warm_build_3d(G, classes, desc, blob, K)
+    print("3D warm", st, flush=True)
+    assert st["jobs"] == 2 * K and st["directions"] == 2 * K * N
+    assert st["fallback_jobs"] < 0.2 * st["directions"]
+    fw, sw = G.cache_to_numpy(warm, desc, K)
+    fp, sp = G.cache_to_numpy(plain, desc, K)
+    compare_to_plain(fw, sw, fp, sp, (0, 1))
+    cls = classes.cpu().numpy()
+    fib = O.fibonacci(N)
+    rng = np.random.default_rng(31)
+    for _ in range(24):
+        k, mode, i = int(rng.integers(K)), int(rng.integers(2)), int(rng.integers(N))
+        t0, p0 = cls[k, 11], cls[k, 12]
+        ez = np.array([np.sin(t0) * np.cos(p0), np.sin(t0) * np.sin(p0), np.cos(t0)])
+        f, so = O.solve(cls[k], mode, np.arccos(np.clip(fib[i] @ ez, -1, 1)))
+        assert sw[mode, k, i] == so
+        if so & (O.ST_NO_BRACKET | O.ST_FLUID):
+            continue
+        for name in ("V", "A"):
+            assert abs(fw[O.FIELDS.index(name), mode, k, i] - f[name]) <= 1e-10 * abs(f[name])
+
+
+def test_warm_3d_untrained_surrogate_equals_plain(G):
+    """A random (untrained) surrogate in 3D: directions its polish cannot
+    take go to the plain search; the cache equals the plain build."""
+    C = _C()
+    classes, K = _config5_classes(G)
+    desc = C.cache_desc(dim=3, n_dirs=3000, modes=(0, 1), n_sweep=720)
+    plain = G.build_cache(classes, desc)
+    warm, st = warm_build_3d(G, classes, desc, new_blob(G, random_params(5)), K)
+    print("3D untrained", st, flush=True)
+    assert st["fallback_jobs"] > 0
+    fw, sw = G.cache_to_numpy(warm, desc, K)
+    fp, sp = G.cache_to_numpy(plain, desc, K)
+    compare_to_plain(fw, sw, fp, sp, (0, 1))
