@@ -70,6 +70,9 @@ def lib():
         L.orc_build_cache_3d.argtypes = [P, l, i, u, i, i, P, P]
         L.orc_star_3d.argtypes = [i, d, d, d, i, P, P, P, P, P]
         L.orc_trace_3d.argtypes = [l, l, l, d, d, d, P, i, i, P, P, P, l, P, P, P, P, P]
+        L.orc_build_cache_slow_2d.argtypes = [P, l, i, u, i, P, P]
+        L.orc_slow_lookup.argtypes = [l, i, P, P, P, i, P, P, d, d, P]
+        L.orc_trace_2d_slow.argtypes = [l, l, d, d, P, l, i, i, P, P, P, P, P, l, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -286,4 +289,54 @@ def trace_3d(nx, ny, nz, hx, hy, hz, class_id, R, V, A, status, src, N=N_FIB,
                             _p(out["predA"]), _p(out["tstar"]))
     if rc:
         raise ValueError(f"orc_trace_3d failed rc={rc}")
+    return out
+
+
+# ------------------------------------------------- slowness-sampled cache --
+
+def build_cache_slow_2d(classes, n=360, mode_mask=0b111, reading=MEV):
+    """The slowness-sampled cache: entry s of a class is the homogeneous
+    solution at real slowness angle s 2 pi / n in the class's axis frame.
+    Returns (fields [NF][3][K][n], status [3][K][n])."""
+    classes = np.ascontiguousarray(np.atleast_2d(classes), dtype=np.float64)
+    K = classes.shape[0]
+    fields = np.full((NF, 3, K, n), np.nan)
+    status = np.zeros((3, K, n), dtype=np.int32)
+    rc = lib().orc_build_cache_slow_2d(_p(classes), K, n, mode_mask, reading, _p(fields),
+                                       _p(status))
+    if rc:
+        raise ValueError(f"orc_build_cache_slow_2d failed rc={rc}")
+    return fields, status
+
+
+def slow_lookup(RX, RZ, status, R, hx, hz):
+    """[K][|O|] sample of each class whose stored ray direction is closest
+    to each star offset (-1 if none)."""
+    RX = np.ascontiguousarray(RX, dtype=np.float64)
+    RZ = np.ascontiguousarray(RZ, dtype=np.float64)
+    st = np.ascontiguousarray(status, dtype=np.int32)
+    K, n = RX.shape
+    ox, oz, _, _ = star_2d(R, hx, hz, 4)
+    best = np.zeros((K, ox.size), np.int32)
+    lib().orc_slow_lookup(K, n, _p(RX), _p(RZ), _p(st), ox.size, _p(ox), _p(oz), hx, hz,
+                          _p(best))
+    return best
+
+
+def trace_2d_slow(nx, nz, hx, hz, class_id, R, f_mode, st_mode, src):
+    """Dijkstra on a slowness-sampled cache slice: f_mode = fields[:, mode]
+    ([NF][K][n]), st_mode = status[mode].  Returns tauR, tauI, predP,
+    predA, tstar."""
+    n_nodes = nx * nz
+    cid = np.ascontiguousarray(class_id, dtype=np.int32).reshape(-1)
+    K, n = st_mode.shape
+    V, A, RX, RZ = (np.ascontiguousarray(f_mode[i], dtype=np.float64) for i in (0, 1, 3, 4))
+    st = np.ascontiguousarray(st_mode, dtype=np.int32)
+    out = {k: np.zeros(n_nodes) for k in ("tauR", "tauI", "tstar")}
+    out.update({k: np.zeros(n_nodes, np.int32) for k in ("predP", "predA")})
+    rc = lib().orc_trace_2d_slow(nx, nz, hx, hz, _p(cid), K, R, n, _p(V), _p(A), _p(RX), _p(RZ),
+                                 _p(st), int(src), _p(out["tauR"]), _p(out["tauI"]),
+                                 _p(out["predP"]), _p(out["predA"]), _p(out["tstar"]))
+    if rc:
+        raise ValueError(f"orc_trace_2d_slow failed rc={rc}")
     return out

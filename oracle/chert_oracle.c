@@ -729,6 +729,9 @@ typedef struct {
   const int32_t *col;   /* direction -> column */
   const double *V, *A;  /* [class][column] for one mode */
   const int32_t *st;    /* [class][column] */
+  const int32_t *best;  /* slowness-sampled caches: [class][offset] column of
+                           the closest stored ray direction (-1: none);
+                           NULL for ray-direction caches */
 } graph_t;
 
 static long class_of(const graph_t *g, long node) {
@@ -744,13 +747,20 @@ static int entry_usable(const graph_t *g, long k, int c) {
  * field 1 = attenuation.  Not usable -> +inf. */
 static double edge_weight(const graph_t *g, int field, long i, long j, int o) {
   long ki = class_of(g, i), kj = class_of(g, j);
-  int c = g->col[g->bin[o]];
-  if (!entry_usable(g, ki, c) || !entry_usable(g, kj, c)) return INFINITY;
+  int ci, cj;
+  if (g->best) { /* each endpoint its own closest stored direction */
+    ci = g->best[ki * g->n_off + o];
+    cj = g->best[kj * g->n_off + o];
+    if (ci < 0 || cj < 0) return INFINITY;
+  } else {
+    ci = cj = g->col[g->bin[o]];
+  }
+  if (!entry_usable(g, ki, ci) || !entry_usable(g, kj, cj)) return INFINITY;
   if (field == 0) {
-    double vbar = 0.5 * (g->V[ki * g->n_cols + c] + g->V[kj * g->n_cols + c]);
+    double vbar = 0.5 * (g->V[ki * g->n_cols + ci] + g->V[kj * g->n_cols + cj]);
     return g->L[o] / vbar;
   }
-  double abar = 0.5 * (g->A[ki * g->n_cols + c] + g->A[kj * g->n_cols + c]);
+  double abar = 0.5 * (g->A[ki * g->n_cols + ci] + g->A[kj * g->n_cols + cj]);
   return g->L[o] * abar;
 }
 
@@ -934,6 +944,143 @@ int orc_trace_2d(long nx, long nz, double hx, double hz,
                  int32_t *hopA) {
   return orc_trace_2d_cols(nx, nz, hx, hz, class_id, R, n_dirs, NULL, 0, V, A,
                            st, src, tauR, tauI, predP, predA, tstar, hopP, hopA);
+}
+
+/* ------------------------------------------------------------------------ */
+/* O-16  the slowness-sampled cache (eq 26 read literally) and its lookup   */
+/* ------------------------------------------------------------------------ */
+
+/* Entry s of class k holds the homogeneous solution whose real slowness
+ * angle, in the class's symmetry-axis frame (eq 36), is theta_R = s 2pi/n:
+ * theta_I is the homogeneity root nearest 0 in [-30, 30] deg (eq 9), the ray
+ * quantities follow (eqs 10-11) with the ray direction rotated to the
+ * global frame, and the residual field is |h| (no target direction).  No
+ * root: NO_BRACKET.  fields: [ORC_NF][3][n_classes][n]; status [3][K][n]. */
+int orc_build_cache_slow_2d(const double *classes, long n_classes, int n,
+                            unsigned mode_mask, int reading, double *fields,
+                            int32_t *status) {
+  if (n < 4) return 1;
+  long stride = 3L * n_classes * n;
+  for (int mode = 0; mode < 3; ++mode) {
+    if (!(mode_mask & (1u << mode))) continue;
+    for (long k = 0; k < n_classes; ++k) {
+      const double *cls = classes + 13 * k;
+      medium_t m;
+      load_medium(cls, &m);
+      long base = ((long)mode * n_classes + k) * n;
+      int fluid = (mode != ORC_QP) && (cls[3] == 0.0 || (mode == ORC_QSH && cls[4] == 0.0));
+      for (int q = 0; q < n; ++q) {
+        if (fluid) {
+          write_invalid(fields, stride, base + q);
+          status[base + q] = ORC_ST_FLUID;
+          continue;
+        }
+        double thR = q * (2.0 * ORC_PI / n);
+        double thI;
+        if (theta_imag(&m, mode, reading, thR, &thI) != 0) {
+          write_invalid(fields, stride, base + q);
+          status[base + q] = ORC_ST_NO_BRACKET;
+          continue;
+        }
+        eval_t e;
+        energy_velocity(&m, mode, reading, thR, thI, &e);
+        entry_t en;
+        ray_quantities(&e, &en);
+        en.thR = thR;
+        en.thI = thI;
+        en.res = theta_i_zero(&m, mode) ? 0.0 : fabs(homog_residual(&e));
+        int st = ORC_ST_OK;
+        if (!(en.A >= 0.0) || !isfinite(en.V) || !(en.V > 0.0)) st |= ORC_ST_NONPHYS;
+        if (!(en.res <= ORC_RESID_TOL)) st |= ORC_ST_NOCONV;
+        write_entry(fields, stride, base + q, &en, m.tilt);
+        status[base + q] = st;
+      }
+    }
+  }
+  return 0;
+}
+
+/* The closest stored ray direction of every class to every star offset
+ * (text after eq 27: the normalised dot product): best[k][o] = the sample
+ * whose r-hat (global frame) has the largest dot product with the edge's
+ * unit vector, the lowest index on ties, among samples that hold a ray
+ * direction (no NO_BRACKET, no FLUID); -1 if none does. */
+int orc_slow_lookup(long n_classes, int n, const double *RX, const double *RZ,
+                    const int32_t *st, int n_off, const int32_t *ox,
+                    const int32_t *oz, double hx, double hz, int32_t *best) {
+  for (int o = 0; o < n_off; ++o) {
+    double ex = ox[o] * hx, ez = oz[o] * hz;
+    double len = sqrt(ex * ex + ez * ez);
+    double dx = ex / len, dz = ez / len;
+    for (long k = 0; k < n_classes; ++k) {
+      int b = -1;
+      double bd = 0.0;
+      for (int q = 0; q < n; ++q) {
+        if (st[k * n + q] & (ORC_ST_NO_BRACKET | ORC_ST_FLUID)) continue;
+        double dd = RX[k * n + q] * dx + RZ[k * n + q] * dz;
+        if (b < 0 || dd > bd) {
+          b = q;
+          bd = dd;
+        }
+      }
+      best[k * n_off + o] = b;
+    }
+  }
+  return 0;
+}
+
+/* Dijkstra (O-10..O-12) for one mode of a slowness-sampled cache: slice
+ * V, A, RX, RZ, status [K][n]; class map required. */
+int orc_trace_2d_slow(long nx, long nz, double hx, double hz, const int32_t *class_id,
+                      long n_classes, int R, int n, const double *V, const double *A,
+                      const double *RX, const double *RZ, const int32_t *st, long src,
+                      double *tauR, double *tauI, int32_t *predP, int32_t *predA,
+                      double *tstar) {
+  long nn = nx * nz;
+  if (src < 0 || src >= nn || R < 1 || !class_id) return 1;
+  int n_off = orc_star_2d(R, hx, hz, 4, NULL, NULL, NULL, NULL);
+  int32_t *ox = (int32_t *)malloc(sizeof(int32_t) * n_off);
+  int32_t *oz = (int32_t *)malloc(sizeof(int32_t) * n_off);
+  int32_t *bin = (int32_t *)malloc(sizeof(int32_t) * n_off);
+  double *L = (double *)malloc(sizeof(double) * n_off);
+  int32_t *best = (int32_t *)malloc(sizeof(int32_t) * (size_t)n_classes * n_off);
+  double *t = (double *)malloc(sizeof(double) * (size_t)nn);
+  int32_t *pr = (int32_t *)malloc(sizeof(int32_t) * (size_t)nn);
+  int32_t *hp = (int32_t *)malloc(sizeof(int32_t) * (size_t)nn);
+  long *ord = (long *)malloc(sizeof(long) * (size_t)nn);
+  int rc = 0;
+  if (!ox || !oz || !bin || !L || !best || !t || !pr || !hp || !ord) { rc = 2; goto out; }
+  orc_star_2d(R, hx, hz, 4, ox, oz, L, bin);
+  orc_slow_lookup(n_classes, n, RX, RZ, st, n_off, ox, oz, hx, hz, best);
+  graph_t g = {.nx = nx, .nz = nz, .n_off = n_off, .ox = ox, .oz = oz, .bin = bin,
+               .ny = 1, .oy = NULL, .L = L, .cls = class_id, .n_cols = n, .col = NULL,
+               .V = V, .A = A, .st = st, .best = best};
+  for (int field = 0; field < 2; ++field) {
+    double *out_t = field ? tauI : tauR;
+    int32_t *out_p = field ? predA : predP;
+    int want_ts = (field == 0 && tstar != NULL);
+    if (!out_t && !out_p && !want_ts) continue;
+    if (dijkstra(&g, field, src, t)) { rc = 2; goto out; }
+    long nr = 0;
+    predecessors(&g, field, src, t, pr, hp, ord, &nr);
+    if (out_p) memcpy(out_p, pr, sizeof(int32_t) * (size_t)nn);
+    if (want_ts) {
+      for (long i = 0; i < nn; ++i) tstar[i] = INFINITY;
+      tstar[src] = 0.0;
+      for (long q = 1; q < nr; ++q) {
+        long j = ord[q], i = pr[j];
+        long dx = (j % nx) - (i % nx), dz = (j / nx) - (i / nx);
+        int oo = -1;
+        for (int o = 0; o < n_off; ++o)
+          if (ox[o] == dx && oz[o] == dz) { oo = o; break; }
+        tstar[j] = tstar[i] + edge_weight(&g, 1, i, j, oo);
+      }
+    }
+    if (out_t) memcpy(out_t, t, sizeof(double) * (size_t)nn);
+  }
+out:
+  free(ox); free(oz); free(bin); free(L); free(best); free(t); free(pr); free(hp); free(ord);
+  return rc;
 }
 
 /* ------------------------------------------------------------------------ */
