@@ -160,14 +160,34 @@ typedef struct chert_cache_desc {
                          (Newton steps, then the halvings of the bisection
                          fallback); >= 0 (0 = 12 Newton steps and 200
                          halvings)                                          */
-  int32_t reserved;   /* must be 0                                          */
+  int32_t sampling;   /* CHERT_SAMPLE_RAY (0): column d holds the solution
+                         whose ray direction is d 2pi/n_dirs (above);
+                         CHERT_SAMPLE_SLOWNESS (1): column s holds the
+                         solution at real slowness angle s 2pi/n_dirs in the
+                         class's symmetry-axis frame (eq 26 read literally;
+                         2D class caches only, no subset), and an edge reads,
+                         at each endpoint, the column whose stored ray
+                         direction is closest to the edge (see below)      */
   chert_cache_stats *stats_dev; /* nullable device struct: the build calls
                          overwrite it with their counters (after the
                          entries, on the same stream)                       */
 } chert_cache_desc;
-/* The trace calls read dim, n_dirs, mode_mask and the subset of a
- * descriptor; the solver fields (kernel, n_sweep, resid_tol, max_iter,
+/* The trace calls read dim, n_dirs, mode_mask, sampling and the subset of
+ * a descriptor; the solver fields (kernel, n_sweep, resid_tol, max_iter,
  * stats_dev) matter only to the build calls. */
+enum { CHERT_SAMPLE_RAY = 0, CHERT_SAMPLE_SLOWNESS = 1 };
+/* Slowness-sampled caches: column s of (mode, class) is the homogeneous
+ * solution at theta_R = s 2 pi / n_dirs (symmetry-axis frame): theta_I is
+ * the homogeneity root nearest 0 in [-30, 30] deg (NO_BRACKET if none),
+ * the ray quantities follow (eqs 10-11), RX/RZ hold the ray direction in
+ * the global frame and RES the homogeneity residual.  n_sweep is not used.
+ * In a trace, the edge i -> j with offset o reads column b_k(o) of each
+ * endpoint's class k: the column whose stored ray direction has the largest
+ * dot product with the edge's unit vector o / |o| (lowest column on ties;
+ * columns with NO_BRACKET or FLUID are not candidates), then eqs 28-30
+ * with the two columns:
+ *   w_R = L_o / (0.5 (V[k_i][b_ki(o)] + V[k_j][b_kj(o)]))
+ * (unusable entries make the edge impassable, as above). */
 
 /* Field order of the cache arrays. */
 enum {
@@ -186,7 +206,8 @@ enum {
  * n_cols = n_subset if a subset is given, else n_dirs:
  *   [0, 256)            header: uint32 magic 'CHRT' (0x54524843), uint32
  *                       version (1), int32 dim, n_dirs, mode_mask, kernel,
- *                       n_sweep, n_subset, int64 n_classes; rest zero.
+ *                       n_sweep, n_subset, int64 n_classes, int32
+ *                       sampling; rest zero.
  *   fields_offset       double fields[CHERT_NF][3][n_classes][n_cols]
  *   status_offset       int32 status[3][n_classes][n_cols]
  * Slots of modes outside mode_mask are left as they were.  The blob is

@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "HIP",
                 4: "NO_CONVERGENCE", 5: "CAPACITY", 6: "UNREACHABLE", 7: "CYCLE", 8: "ABORTED"}
 QP, QSV, QSH = 0, 1, 2
 KERNEL_MEV, KERNEL_OEV = 0, 1
+SAMPLE_RAY, SAMPLE_SLOWNESS = 0, 1
 ST_OK, ST_NO_BRACKET, ST_ILL, ST_FLUID, ST_NONPHYS, ST_NOCONV = 0, 1, 2, 4, 8, 16
 ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_NO_CONVERGENCE, ERR_ABORTED = 1, 2, 4, 8
 FIELDS = ("V", "A", "Q", "rx", "rz", "thR", "thI", "res")
@@ -85,7 +86,7 @@ class CacheDesc(ctypes.Structure):
                 ("mode_mask", ctypes.c_uint32), ("kernel", ctypes.c_int32),
                 ("n_sweep", ctypes.c_int32), ("n_subset", ctypes.c_int32),
                 ("subset_host", ctypes.c_void_p), ("resid_tol", ctypes.c_double),
-                ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("sampling", ctypes.c_int32),
                 ("stats_dev", ctypes.c_void_p)]
 
     @property
@@ -243,11 +244,12 @@ def chert_class_from_thomsen(vp0, vs0, rho, eps, delta, gamma, tilt, azimuth, qp
 
 
 def cache_desc(n_dirs=360, modes=(QP, QSV, QSH), kernel=KERNEL_MEV, n_sweep=1440, dim=2,
-               subset=None, resid_tol=0.0, max_iter=0, stats=None):
+               subset=None, resid_tol=0.0, max_iter=0, stats=None, sampling=0):
     """subset: ascending direction indices closed under reversal (kept
     referenced by the descriptor), e.g. star_subset(radius, hx, hz);
     resid_tol / max_iter: the solver's residual cap and bracket step cap
-    (0 = library defaults); stats: a device tensor of at least
+    (0 = library defaults); sampling: SAMPLE_RAY (ray-direction columns)
+    or SAMPLE_SLOWNESS (slowness-angle columns); stats: a device tensor of at least
     CACHE_STATS_BYTES bytes that the build calls overwrite with a
     chert_cache_stats (read it with cache_stats_of)."""
     mask = 0
@@ -256,11 +258,11 @@ def cache_desc(n_dirs=360, modes=(QP, QSV, QSH), kernel=KERNEL_MEV, n_sweep=1440
     sp = stats.data_ptr() if stats is not None else None
     if subset is None:
         d = CacheDesc(dim, n_dirs, mask, kernel, n_sweep, 0, None, float(resid_tol),
-                      int(max_iter), 0, sp)
+                      int(max_iter), int(sampling), sp)
     else:
         sub = np.ascontiguousarray(subset, dtype=np.int32)
         d = CacheDesc(dim, n_dirs, mask, kernel, n_sweep, int(sub.size), sub.ctypes.data,
-                      float(resid_tol), int(max_iter), 0, sp)
+                      float(resid_tol), int(max_iter), int(sampling), sp)
         d._subset = sub
     d._stats = stats
     return d

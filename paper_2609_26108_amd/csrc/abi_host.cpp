@@ -315,7 +315,10 @@ extern "C" int chert_cache_layout_of(const chert_cache_desc* d, int64_t n_classe
   if (!(d->resid_tol >= 0.0) || !isfinite(d->resid_tol))
     return fail(CHERT_ERR_INVALID_ARG, "resid_tol must be finite and >= 0");
   if (d->max_iter < 0) return fail(CHERT_ERR_INVALID_ARG, "max_iter must be >= 0");
-  if (d->reserved != 0) return fail(CHERT_ERR_INVALID_ARG, "reserved field must be 0");
+  if (d->sampling != CHERT_SAMPLE_RAY && d->sampling != CHERT_SAMPLE_SLOWNESS)
+    return fail(CHERT_ERR_INVALID_ARG, "sampling must be CHERT_SAMPLE_RAY or _SLOWNESS");
+  if (d->sampling == CHERT_SAMPLE_SLOWNESS && (d->dim != 2 || d->n_subset != 0))
+    return fail(CHERT_ERR_UNSUPPORTED, "slowness-sampled caches are 2D, without subsets");
   if (d->n_subset != 0) {
     if (d->n_subset < 0 || d->n_subset > kMaxSubset || !d->subset_host || (d->n_subset & 1))
       return fail(CHERT_ERR_INVALID_ARG, "subset needs 2..512 (even) directions");

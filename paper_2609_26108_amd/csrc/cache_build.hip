@@ -1116,6 +1116,50 @@ __global__ void __launch_bounds__(64) k_warm_fold(WarmArgs w) {
   }
 }
 
+// ------------------------------------------- slowness-sampled caches
+// Column s of (mode, class): the homogeneous solution at real slowness
+// angle theta_R = s 2 pi / n_cols in the class's symmetry-axis frame (eq 26
+// with the slowness angle as index): theta_I is the homogeneity root
+// nearest 0 (eq 9), the ray quantities follow (eqs 10-11) and the ray
+// direction is rotated to the global frame; RES is |h|.  One lane per
+// (mode, class, column).
+__global__ void __launch_bounds__(256) k_build_slow(SolveArgs a) {
+  const int64_t total = (int64_t)a.n_modes * a.n_classes * a.n_cols;
+  const int64_t stride = 3 * a.n_classes * (int64_t)a.n_cols;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int q = (int)(t % a.n_cols);
+    const int64_t job = t / a.n_cols;
+    const int64_t k = job % a.n_classes;
+    const int mode = a.modes[job / a.n_classes];
+    const chert_class c = a.classes[k];
+    const int64_t idx = ((int64_t)mode * a.n_classes + k) * a.n_cols + q;
+    const int32_t blocked = class_block(c, mode);
+    if (blocked) {
+      store_invalid(a, idx, stride, blocked);
+      continue;
+    }
+    const Medium m = load_medium(c);
+    const double thR = q * (kTwoPi / a.n_cols);
+    double sr, cr, thI;
+    sincos(thR, &sr, &cr);
+    if (!theta_imag_sc(m, mode, a.kernel, sr, cr, &thI)) {
+      store_invalid(a, idx, stride, CHERT_ST_NO_BRACKET);
+      continue;
+    }
+    const Vel v = energy_velocity(m, mode, a.kernel, thR, thI);
+    Entry e;
+    ray_quantities(v, &e);
+    e.thR = thR;
+    e.thI = thI;
+    e.res = theta_i_zero(m, mode) ? 0.0 : fabs(homog_residual(v));
+    int32_t st = CHERT_ST_OK;
+    if (!(e.A >= 0.0) || !isfinite(e.V) || !(e.V > 0.0)) st |= CHERT_ST_NONPHYS;
+    if (!(e.res <= a.resid_tol)) st |= CHERT_ST_NOCONV;
+    store_entry(a, idx, stride, e, m.tilt, st);
+  }
+}
+
 // ------------------------------------------------------- 3D warm start
 // Surrogate-started 3D caches: every (mode, class, Fibonacci direction) is
 // polished on its own from its prediction (one lane each) under the same
@@ -1288,7 +1332,7 @@ __global__ void k_warm_zero(int32_t* fb_len, int32_t* win_len, unsigned long lon
 
 __global__ void k_write_header(uint8_t* cache, int32_t dim, int32_t n_dirs, uint32_t mask,
                                int32_t kernel, int32_t n_sweep, int32_t n_subset,
-                               int64_t n_classes) {
+                               int64_t n_classes, int32_t sampling) {
   int t = threadIdx.x;
   uint32_t* w = reinterpret_cast<uint32_t*>(cache);
   if (t < 64) w[t] = 0u;
@@ -1303,6 +1347,7 @@ __global__ void k_write_header(uint8_t* cache, int32_t dim, int32_t n_dirs, uint
     w[6] = (uint32_t)n_sweep;
     w[7] = (uint32_t)n_subset;
     *reinterpret_cast<int64_t*>(cache + 32) = n_classes;
+    w[10] = (uint32_t)sampling;
   }
 }
 
@@ -1469,6 +1514,7 @@ static int launch_status() {
 extern "C" size_t chert_build_cache_workspace_bytes(const chert_cache_desc* d,
                                                     int64_t n_classes) {
   if (!d || n_classes <= 0 || d->n_sweep <= 0) return 0;
+  if (d->sampling == CHERT_SAMPLE_SLOWNESS) return 0;                     // no sweep table
   if (d->dim != 3 && n_jobs_of(d, n_classes) >= kFusedJobs) return 0;  // table stays in LDS
   return (size_t)n_jobs_of(d, n_classes) * (size_t)d->n_sweep * sizeof(double2);
 }
@@ -1552,9 +1598,15 @@ static int build_cache(const chert_cache_desc* d, const chert_class* classes_dev
   const SolveArgs so = solve_args(d, classes_dev, n_classes, cache, lay, workspace_dev);
 
   CHERT_LAUNCH("k_write_header", k_write_header, dim3(1), dim3(64), 0, s, cache, d->dim,
-               d->n_dirs, d->mode_mask, d->kernel, d->n_sweep, d->n_subset, n_classes);
+               d->n_dirs, d->mode_mask, d->kernel, d->n_sweep, d->n_subset, n_classes,
+                 d->sampling);
   const int64_t jobs = (int64_t)so.n_modes * n_classes;
-  if (jobs >= kFusedJobs && d->dim != 3) {
+  if (d->sampling == CHERT_SAMPLE_SLOWNESS) {
+    const int64_t total = jobs * so.n_cols;
+    const int64_t blocks = (total + 255) / 256 > 65536 ? 65536 : (total + 255) / 256;
+    if (total > 0)
+      CHERT_LAUNCH("k_build_slow", k_build_slow, dim3((unsigned)blocks), dim3(256), 0, s, so);
+  } else if (jobs >= kFusedJobs && d->dim != 3) {
     CHERT_LAUNCH("k_build_fused", k_build_fused, dim3((unsigned)jobs), dim3(kNodeThreads),
                  (size_t)d->n_sweep * sizeof(double2), s, so, (const int32_t*)nullptr,
                  (const int32_t*)nullptr, jobs);
@@ -1620,6 +1672,8 @@ extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
   chert_cache_layout lay;
   int rc = common_checks(d, classes_dev, n_classes, cache_dev, &lay);
   if (rc != CHERT_OK) return rc;
+  if (d->sampling != CHERT_SAMPLE_RAY)
+    return fail(CHERT_ERR_UNSUPPORTED, "surrogate-started builds fill ray-direction caches");
   if (!blob_dev || ((uintptr_t)blob_dev & 255u))
     return fail(CHERT_ERR_INVALID_ARG, "null or unaligned surrogate blob");
   if (!(resid_tol >= 0.0)) return fail(CHERT_ERR_INVALID_ARG, "negative residual tolerance");
@@ -1648,7 +1702,8 @@ extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
     w.stats = stats_dev ? (unsigned long long*)stats_dev : (unsigned long long*)(ws + 64);
     w.resid_tol = resid_tol > 0.0 ? resid_tol : 1e-11;
     CHERT_LAUNCH("k_write_header", k_write_header, dim3(1), dim3(64), 0, s, cache, d->dim,
-                 d->n_dirs, d->mode_mask, d->kernel, d->n_sweep, d->n_subset, n_classes);
+                 d->n_dirs, d->mode_mask, d->kernel, d->n_sweep, d->n_subset, n_classes,
+                 d->sampling);
     CHERT_LAUNCH("k_warm_zero", k_warm_zero, dim3(1), dim3(64), 0, s, w.fb_len, w.fb_len + 1,
                  w.stats);
     if (rows > 0) {
@@ -1701,7 +1756,8 @@ extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
   w.resid_tol = resid_tol > 0.0 ? resid_tol : 1e-11;
 
   CHERT_LAUNCH("k_write_header", k_write_header, dim3(1), dim3(64), 0, s, cache, d->dim,
-               d->n_dirs, d->mode_mask, d->kernel, d->n_sweep, d->n_subset, n_classes);
+               d->n_dirs, d->mode_mask, d->kernel, d->n_sweep, d->n_subset, n_classes,
+                 d->sampling);
   CHERT_LAUNCH("k_warm_zero", k_warm_zero, dim3(1), dim3(64), 0, s, w.fb_len, w.win_len,
                w.stats);
   if (jobs > 0 && rows > 0) {

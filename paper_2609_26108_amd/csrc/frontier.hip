@@ -511,6 +511,8 @@ static int make_plan_f(const chert_trace_job* jobs, int n_jobs, const chert_trac
   for (int j = 0; j < n_jobs; ++j) {
     int rc = P->dim == 3 ? validate_job3(jobs[j], outs) : validate_job_2d(jobs[j], outs);
     if (rc) return rc;
+    if (jobs[j].d->sampling != CHERT_SAMPLE_RAY)
+      return fail(CHERT_ERR_UNSUPPORTED, "the node frontier reads ray-direction caches only");
     if (jobs[j].g->radius != jobs[0].g->radius)
       return fail(CHERT_ERR_INVALID_ARG, "all jobs of a batch need the same radius");
   }

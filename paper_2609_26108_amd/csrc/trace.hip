@@ -191,9 +191,11 @@ __device__ __forceinline__ void count_visit(const RelaxArgs& a, int phase, long 
 __global__ void k_check_classes(const int32_t* cls, int64_t n, int K, int32_t* err);
 
 // W[f][ki][kj][o]: eqs 28-30 in this operation order, no contraction.
+// Slowness-sampled caches: column of each endpoint from `best` [K][n_off]
+// (the class's closest stored ray direction, -1: none) instead of col[o].
 __global__ void k_weights(double* W, int K, int n_off, const double* V, const double* A,
                           const int32_t* st, int n_cols, const double* L,
-                          const int32_t* col) {
+                          const int32_t* col, const int32_t* best) {
   int64_t total = 2LL * K * K * n_off;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
@@ -203,11 +205,12 @@ __global__ void k_weights(double* W, int K, int n_off, const double* V, const do
     r /= K;
     int ki = (int)(r % K);
     int f = (int)(r / K);
-    const int b = col[o];
+    const int bi = best ? best[(int64_t)ki * n_off + o] : col[o];
+    const int bj = best ? best[(int64_t)kj * n_off + o] : col[o];
     const int bad = CHERT_ST_NO_BRACKET | CHERT_ST_FLUID | CHERT_ST_NONPHYS | CHERT_ST_NOCONV;
-    int64_t ei = (int64_t)ki * n_cols + b, ej = (int64_t)kj * n_cols + b;
+    int64_t ei = (int64_t)ki * n_cols + bi, ej = (int64_t)kj * n_cols + bj;
     double w;
-    if ((st[ei] & bad) || (st[ej] & bad)) {
+    if (bi < 0 || bj < 0 || (st[ei] & bad) || (st[ej] & bad)) {
       w = INFINITY;
     } else if (f == kFieldR) {
       w = __ddiv_rn(L[o], __dmul_rn(0.5, __dadd_rn(V[ei], V[ej])));
@@ -215,6 +218,37 @@ __global__ void k_weights(double* W, int K, int n_off, const double* V, const do
       w = __dmul_rn(L[o], __dmul_rn(0.5, __dadd_rn(A[ei], A[ej])));
     }
     W[t] = w;
+  }
+}
+
+// The closest stored ray direction of class k to offset o (text after eq
+// 27): the column whose RX/RZ has the largest dot product with o's unit
+// vector (IEEE operations in the order of the definition), lowest column on
+// ties, skipping columns without a ray direction; -1 if none.  One thread
+// per (class, offset).
+__global__ void k_slow_lookup(int32_t* best, int K, int n_cols, const double* RX,
+                              const double* RZ, const int32_t* st, int n_off,
+                              const int32_t* ox, const int32_t* oz, double hx, double hz) {
+  const int64_t total = (int64_t)K * n_off;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int o = (int)(t % n_off);
+    const int64_t k = t / n_off;
+    const double ex = __dmul_rn((double)ox[o], hx), ez = __dmul_rn((double)oz[o], hz);
+    const double len = __dsqrt_rn(__dadd_rn(__dmul_rn(ex, ex), __dmul_rn(ez, ez)));
+    const double dx = __ddiv_rn(ex, len), dz = __ddiv_rn(ez, len);
+    int b = -1;
+    double bd = 0.0;
+    for (int q = 0; q < n_cols; ++q) {
+      const int64_t e = k * n_cols + q;
+      if (st[e] & (CHERT_ST_NO_BRACKET | CHERT_ST_FLUID)) continue;
+      const double dd = __dadd_rn(__dmul_rn(RX[e], dx), __dmul_rn(RZ[e], dz));
+      if (b < 0 || dd > bd) {
+        b = q;
+        bd = dd;
+      }
+    }
+    best[(int64_t)k * n_off + o] = b;
   }
 }
 
@@ -1461,6 +1495,7 @@ struct Plan {
          off_counter = 0, off_key = 0, off_pmin = 0, off_wmin = 0,
          off_err = 0, off_nkey = 0, off_tight = 0, total = 0;
   std::vector<size_t> off_W;  // per job
+  std::vector<size_t> off_best;  // per job: closest-direction table (slowness caches)
   int w_lds_doubles = 0;
 };
 
@@ -1482,6 +1517,8 @@ int validate_job_2d(const chert_trace_job& j, uint32_t outs) {
     return fail(CHERT_ERR_INVALID_ARG, "no class map: the cache must hold one class per node");
   if (j.mode < 0 || j.mode > 2 || !(j.d->mode_mask & (1u << j.mode)))
     return fail(CHERT_ERR_INVALID_ARG, "mode not in the cache");
+  if (j.d->sampling == CHERT_SAMPLE_SLOWNESS && !g->class_id_dev)
+    return fail(CHERT_ERR_UNSUPPORTED, "slowness-sampled caches are class caches");
   if (j.n_src < 1) return fail(CHERT_ERR_INVALID_ARG, "need at least one source");
   if (!j.cache_dev) return fail(CHERT_ERR_INVALID_ARG, "null cache");
   if (!j.src_nodes_host) return fail(CHERT_ERR_INVALID_ARG, "null sources");
@@ -1595,6 +1632,9 @@ static int make_plan(const chert_trace_job* jobs, int n_jobs, const chert_trace_
   P->off_err = off;
   off += 256;
   for (int j = 0; j < n_jobs; ++j) {
+    P->off_best.push_back(off);
+    if (jobs[j].d->sampling == CHERT_SAMPLE_SLOWNESS)
+      off += align256((size_t)jobs[j].n_classes * P->n_off * sizeof(int32_t));
     P->off_W.push_back(off);
     const size_t rows = jobs[j].g->class_id_dev
                             ? (size_t)jobs[j].n_classes * jobs[j].n_classes
@@ -1917,11 +1957,23 @@ static int enqueue(const Prepared& Q, const chert_trace_job* jobs, int n_jobs,
                                        Q.dcol + (size_t)j * kMaxOffsets, n_cols, Vm, Am, Sm, s);
       if (rc) return rc;
     } else {
+      const int32_t* best = nullptr;
+      if (J.d->sampling == CHERT_SAMPLE_SLOWNESS) {
+        const double* RXm = fields + CHERT_F_RX * ent + mslice;
+        const double* RZm = fields + CHERT_F_RZ * ent + mslice;
+        int32_t* bt = (int32_t*)(ws + P.off_best[j]);
+        const int64_t tl = K * P.n_off;
+        CHERT_LAUNCH("k_slow_lookup", k_slow_lookup,
+                     dim3((unsigned)((tl + 255) / 256 > 4096 ? 4096 : (tl + 255) / 256)), dim3(256),
+                     0, s, bt, (int)K, n_cols, RXm, RZm, Sm, P.n_off, (const int32_t*)Q.dox,
+                     (const int32_t*)Q.doz, J.g->hx, J.g->hz);
+        best = bt;
+      }
       int64_t tw = 2 * K * K * P.n_off;
       int64_t blocks = (tw + 255) / 256;
       CHERT_LAUNCH("k_weights", k_weights, dim3((unsigned)(blocks > 65536 ? 65536 : blocks)),
                    dim3(256), 0, s, (double*)(ws + P.off_W[j]), (int)K, P.n_off, Vm, Am, Sm,
-                   n_cols, Q.dL + (size_t)j * kMaxOffsets, Q.dcol + (size_t)j * kMaxOffsets);
+                   n_cols, Q.dL + (size_t)j * kMaxOffsets, Q.dcol + (size_t)j * kMaxOffsets, best);
     }
   }
   if (a.bucket > 0.0) {  // the ordering's unit: smallest edge weight per field
@@ -2173,7 +2225,10 @@ extern "C" int chert_trace_autotune(const chert_trace_job* jobs, int32_t n_jobs,
   const double* bws = three_d ? kTuneBuckets : kTuneBuckets2D;
   const int n_bws = three_d ? (int)(sizeof(kTuneBuckets) / sizeof(double))
                             : (int)(sizeof(kTuneBuckets2D) / sizeof(double));
-  for (int q = 0; q < n_bws; ++q) {
+  bool ray_caches = true;  // the frontier reads ray-direction caches only
+  for (int j = 0; j < n_jobs; ++j)
+    if (jobs[j].d && jobs[j].d->sampling != CHERT_SAMPLE_RAY) ray_caches = false;
+  for (int q = 0; ray_caches && q < n_bws; ++q) {
     chert_trace_opts c = *o;
     c.launch = CHERT_LAUNCH_FRONTIER;
     c.bucket_width = bws[q];

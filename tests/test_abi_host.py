@@ -320,8 +320,8 @@ def test_class_pair_table_index_limit():
 
 
 def test_cache_desc_solver_fields_validated():
-    """resid_tol must be finite and >= 0, max_iter >= 0 and the reserved
-    word 0; each violation is INVALID_ARG before any device work."""
+    """resid_tol must be finite and >= 0, max_iter >= 0 and sampling one of
+    the two kinds; each violation is INVALID_ARG before any device work."""
     C.chert_cache_layout_of(C.cache_desc(resid_tol=1e-12, max_iter=3), 2)
     for kw in ({"resid_tol": -1e-9}, {"resid_tol": float("nan")}, {"resid_tol": float("inf")},
                {"max_iter": -1}):
@@ -329,10 +329,17 @@ def test_cache_desc_solver_fields_validated():
             C.chert_cache_layout_of(C.cache_desc(**kw), 2)
         assert e.value.code == 1
     d = C.cache_desc()
-    d.reserved = 7
+    d.sampling = 7
     with pytest.raises(C.ChertError) as e:
         C.chert_cache_layout_of(d, 2)
     assert e.value.code == 1
+    # slowness-sampled caches are 2D and hold every column
+    C.chert_cache_layout_of(C.cache_desc(sampling=C.SAMPLE_SLOWNESS), 2)
+    for bad in (C.cache_desc(sampling=1, dim=3, n_dirs=300),
+                C.cache_desc(sampling=1, subset=C.star_subset(2, 10.0, 10.0))):
+        with pytest.raises(C.ChertError) as e:
+            C.chert_cache_layout_of(bad, 2)
+        assert e.value.code == 2
 
 
 def test_abi_struct_layouts_match_header(tmp_path):
