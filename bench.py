@@ -21,7 +21,9 @@ The CPU oracle is timed on a fixed subset of the step and extrapolated
 
 Other workloads print their own line: `layered` (the 5-layer model, class
 caches), `complex2d` (per-node caches of the 1701x351 model, k-means
-ablation), `3d` (the 201x201x101 layered model).
+ablation), `3d` (the 201x201x101 layered model), `ablation` (angular step
+and star radius), `local` (the OEV-versus-MEV sweep on rock layer 1 with
+slowness- and ray-sampled caches).
 """
 from __future__ import annotations
 
@@ -122,7 +124,7 @@ def parse():
                    help="complex2d, shots: trace with the default (or given) launch options")
     p.add_argument("--bucket", type=float, default=0.0,
                    help="node-frontier near/far bucket width (units of the smallest weight)")
-    p.add_argument("--workload", choices=("shots", "layered", "complex2d", "3d", "ablation"),
+    p.add_argument("--workload", choices=("shots", "layered", "complex2d", "3d", "ablation", "local"),
                    default="shots",
                    help="shots: 128 shots over 4 uneven per-node grids, surrogate-started "
                         "caches + one batched trace per step (default, the headline line); "
@@ -183,6 +185,9 @@ def main():
         return
     if args.workload == "ablation":
         run_ablation(args)
+        return
+    if args.workload == "local":
+        run_local(args)
         return
     m = W.config2()
     K = len(m.layers)
@@ -1115,6 +1120,161 @@ def run_ablation(args):
     res["value"] = res["complex"]["1deg_R5"]["misfit"]["rms_ms"]
     res["unit"] = "ms RMS tau_R misfit of the 1-degree, radius-5 per-node trace against 0.5 deg / R 6"
     res["higher_is_better"] = False
+    print(json.dumps(res))
+
+
+LOCAL_FINE = 360000  # slowness samples of the timed local sweep (0.001 degree)
+
+
+def rock_layer1_class():
+    """Layer 1 of the paper's rock-property table (the medium of its local
+    kernel benchmark) as a class row: moduli in m^2/s^2, Q per component,
+    vertical symmetry axis."""
+    with open(os.path.join(ROOT, "tests", "golden", "rock_table.txt")) as f:
+        rows = [[float(x) for x in ln.split()[1:]] for ln in f
+                if ln.strip() and not ln.startswith("#")]
+    r = rows[0]
+    return np.array([v * 1e6 for v in r[:5]] + r[5:10] + [2300.0, 0.0, 0.0])
+
+
+def _angle_sweep_stats(f, st, mode, cols):
+    """Range and smoothness of one mode's cache columns `cols` (adjacent
+    samples): theta_I range and its largest step [deg], the largest relative
+    step of V and A, and the status counts."""
+    bad = 1 | 4 | 8 | 16  # NO_BRACKET, FLUID, NONPHYS, NOCONV
+    s = st[mode, 0, cols]
+    ok = (s & bad) == 0
+    thi = np.degrees(f[6, mode, 0, cols])
+    V, A = f[0, mode, 0, cols], f[1, mode, 0, cols]
+    pair = ok[1:] & ok[:-1]
+    out = {"samples": int(len(cols)), "usable": int(ok.sum()),
+           "ill": int(((s & 2) != 0).sum()), "noconv": int(((s & 16) != 0).sum()),
+           "no_bracket": int(((s & 1) != 0).sum())}
+    if ok.any():
+        out["thetaI_deg"] = [float(thi[ok].min()), float(thi[ok].max())]
+    if pair.any():
+        out["max_step_thetaI_deg"] = float(np.abs(np.diff(thi))[pair].max())
+        out["max_rel_step_V"] = float((np.abs(np.diff(V)) / V[:-1])[pair].max())
+        out["max_rel_step_A"] = float((np.abs(np.diff(A)) / np.abs(A[:-1]))[pair].max())
+    return out
+
+
+def run_local(args):
+    """The local kernel benchmark (the paper's OEV-versus-MEV sweep on layer
+    1 of its rock table, eqs 12-14 and 26) and the cache-sampling comparison
+    it motivates: for each reading, the slowness-sampled cache (eq 26 at every
+    real slowness angle) and the ray-direction cache at 1 degree, with the
+    theta_I range and the smoothness of theta_I, V and A over 0-90 degrees;
+    then the slowness sweep at 0.001 degree timed (Hamiltonian solves/s),
+    and traveltimes of the layered model through slowness-sampled and
+    ray-direction caches against each other."""
+    import torch
+    import paper_2609_26108_amd as C
+    import workloads as W
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    cls = torch.from_numpy(rock_layer1_class()[None]).to(dev)
+    modes = (0, 1, 2)
+    names = {0: "qP", 1: "qSV", 2: "qSH"}
+    res = {"metric": METRIC, "workload": "local", "n_gpus": 1, "dtype": "f64",
+           "data": "layer 1 of the paper's rock-property table (tests/golden/rock_table.txt); "
+                   "seeded workloads.config2 for the traveltime comparison",
+           "config": {"workload": "local sweep on rock layer 1: 1-degree caches (slowness- and "
+                                  "ray-sampled, MEV and OEV) and a 0.001-degree slowness sweep; "
+                                  "layered 401x201 @5 m traveltimes through both samplings",
+                      "fine_samples": LOCAL_FINE}}
+    sweep = {}
+    for kname, kern in (("MEV", C.KERNEL_MEV), ("OEV", C.KERNEL_OEV)):
+        for sname, samp in (("slowness", C.SAMPLE_SLOWNESS), ("ray", C.SAMPLE_RAY)):
+            desc = C.cache_desc(n_dirs=360, modes=modes, kernel=kern, sampling=samp)
+            lay = C.chert_cache_layout_of(desc, 1)
+            cache = torch.zeros(lay.total_bytes, dtype=torch.uint8, device=dev)
+            ws = torch.empty(max(C.chert_build_cache_workspace_bytes(desc, 1), 1),
+                             dtype=torch.uint8, device=dev)
+            C.chert_build_cache(desc, cls, 1, cache, ws, stream=stream)
+            torch.cuda.synchronize()
+            f, st = C.cache_views(cache, desc, 1)
+            f, st = f.cpu().numpy(), st.cpu().numpy()
+            sweep[f"{kname}_{sname}"] = {names[m]: _angle_sweep_stats(f, st, m, np.arange(91))
+                                         for m in modes}
+    res["sweep_1deg_0_90"] = sweep
+
+    timing = {}
+    for kname, kern in (("MEV", C.KERNEL_MEV), ("OEV", C.KERNEL_OEV)):
+        desc = C.cache_desc(n_dirs=LOCAL_FINE, modes=modes, kernel=kern,
+                            sampling=C.SAMPLE_SLOWNESS)
+        lay = C.chert_cache_layout_of(desc, 1)
+        cache = torch.zeros(lay.total_bytes, dtype=torch.uint8, device=dev)
+        ws = torch.empty(1, dtype=torch.uint8, device=dev)
+        C.chert_build_cache(desc, cls, 1, cache, ws, stream=stream)  # warm-up
+        t = []
+        for _ in range(max(args.steps, 1)):
+            ev = _events(torch, stream)
+            C.chert_build_cache(desc, cls, 1, cache, ws, stream=stream)
+            t.append(_elapsed(torch, ev, stream))
+        ts = float(np.median(t))
+        _, st = C.cache_views(cache, desc, 1)
+        st = st.cpu().numpy()
+        timing[kname] = {"build_s": ts, "solves_per_s": 3 * LOCAL_FINE / ts,
+                         "usable": int(((st & (1 | 4 | 8 | 16)) == 0).sum())}
+    res["fine_sweep"] = timing
+
+    # traveltimes through both samplings (MEV, 1 degree, class caches)
+    m = W.config2()
+    K = len(m.layers)
+    lcls = torch.from_numpy(np.stack([C.chert_class_from_thomsen(*L.thomsen_args()).as_array()
+                                      for L in m.layers])).to(dev)
+    cid = torch.from_numpy(m.class_id.reshape(-1).astype(np.int32)).to(dev)
+    grid = C.make_grid(m.nx, m.nz, m.hx, m.hz, m.radius, cid)
+    taus = {}
+    for sname, samp in (("slowness", C.SAMPLE_SLOWNESS), ("ray", C.SAMPLE_RAY)):
+        desc = C.cache_desc(n_dirs=360, modes=m.modes, sampling=samp)
+        lay = C.chert_cache_layout_of(desc, K)
+        cache = torch.zeros(lay.total_bytes, dtype=torch.uint8, device=dev)
+        ws = torch.empty(max(C.chert_build_cache_workspace_bytes(desc, K), 1), dtype=torch.uint8,
+                         device=dev)
+        C.chert_build_cache(desc, lcls, K, cache, ws, stream=stream)
+        ev = _events(torch, stream)
+        C.chert_build_cache(desc, lcls, K, cache, ws, stream=stream)
+        tb = _elapsed(torch, ev, stream)
+        b = C.Batch()
+        outs = {}
+        for mode in m.modes:
+            outs[mode] = (torch.empty((1, m.n_nodes), dtype=torch.float64, device=dev),
+                          torch.empty((1, m.n_nodes), dtype=torch.float64, device=dev))
+            b.add(desc, cache, K, grid, mode, m.sources, tau_r=outs[mode][0],
+                  tau_i=outs[mode][1])
+        o = C.trace_opts(C.OUT_TAU_R | C.OUT_TAU_I)
+        tws = torch.empty(C.chert_trace_batch_workspace_bytes(b, o), dtype=torch.uint8,
+                          device=dev)
+        C.chert_trace_batch(b, o, tws, stream=stream)
+        ev = _events(torch, stream)
+        C.chert_trace_batch(b, o, tws, stream=stream)
+        tt = _elapsed(torch, ev, stream)
+        taus[sname] = ({mode: (outs[mode][0][0].clone(), outs[mode][1][0].clone())
+                        for mode in m.modes}, tb, tt)
+    a, b_ = taus["slowness"][0], taus["ray"][0]
+    res["layered_slowness_vs_ray"] = {
+        "build_s": {"slowness": taus["slowness"][1], "ray": taus["ray"][1]},
+        "trace_s": {"slowness": taus["slowness"][2], "ray": taus["ray"][2]},
+        "tauR_misfit": {names[md]: _misfit(a[md][0], b_[md][0]) for md in m.modes},
+        "tauI_misfit": {names[md]: _misfit(a[md][1], b_[md][1]) for md in m.modes}}
+
+    if not args.no_cpu:
+        import oracle as O
+        t0 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t0 < 10.0:
+            O.build_cache_slow_2d(rock_layer1_class()[:13], n=3600, mode_mask=0b111)
+            reps += 1
+        el = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": reps * 3 * 3600 / el, "unit": "Hamiltonian solves/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"{reps} slowness-sampled builds of rock layer 1, "
+                                         "3 modes x 3600 samples (MEV)"}
+    res["value"] = timing["MEV"]["solves_per_s"]
+    res["unit"] = "Hamiltonian solves/s (slowness-sampled MEV, rock layer 1, 3 modes)"
+    res["higher_is_better"] = True
     print(json.dumps(res))
 
 
