@@ -71,6 +71,8 @@ def lib():
         L.orc_star_3d.argtypes = [i, d, d, d, i, P, P, P, P, P]
         L.orc_trace_3d.argtypes = [l, l, l, d, d, d, P, i, i, P, P, P, l, P, P, P, P, P]
         L.orc_build_cache_slow_2d.argtypes = [P, l, i, u, i, P, P]
+        L.orc_trace_cells_2d.argtypes = [l, l, i, d, d, P, l, i, i, P, P, P, P, P, l, i,
+                                         P, P, P, P, P]
         L.orc_slow_lookup.argtypes = [l, i, P, P, P, i, P, P, d, d, P]
         L.orc_trace_2d_slow.argtypes = [l, l, d, d, P, l, i, i, P, P, P, P, P, l, P, P, P, P, P]
         _lib = L
@@ -339,4 +341,38 @@ def trace_2d_slow(nx, nz, hx, hz, class_id, R, f_mode, st_mode, src):
                                  _p(out["predP"]), _p(out["predA"]), _p(out["tstar"]))
     if rc:
         raise ValueError(f"orc_trace_2d_slow failed rc={rc}")
+    return out
+
+
+def cell_lattice(ncx, ncz, cn):
+    """(NX, NZ, mask): lattice size of a cell network and which lattice
+    points are nodes (on a cell edge)."""
+    NX, NZ = ncx * cn + 1, ncz * cn + 1
+    ix = np.arange(NX)[None, :]
+    iz = np.arange(NZ)[:, None]
+    return NX, NZ, ((ix % cn == 0) | (iz % cn == 0))
+
+
+def trace_cells_2d(ncx, ncz, cn, hx, hz, class_id, f_mode, st_mode, src, sampling=0,
+                   block=False):
+    """Cell network (nodes on cell edges, all pairs within a cell; eqs 23-32):
+    f_mode = fields[:, mode] ([NF][K][n_cols]), st_mode = status[mode];
+    sampling 0 = ray-direction cache, 1 = slowness-sampled cache; block =
+    the block marching instead of node Dijkstra.  Returns lattice-sized
+    tauR, tauI, predP, predA, tstar."""
+    NX, NZ, _ = cell_lattice(ncx, ncz, cn)
+    n = NX * NZ
+    cid = np.ascontiguousarray(class_id, dtype=np.int32).reshape(-1)
+    assert cid.size == n
+    K, nc = st_mode.shape
+    V, A, RX, RZ = (np.ascontiguousarray(f_mode[i], dtype=np.float64) for i in (0, 1, 3, 4))
+    st = np.ascontiguousarray(st_mode, dtype=np.int32)
+    out = {k: np.zeros(n) for k in ("tauR", "tauI", "tstar")}
+    out.update({k: np.zeros(n, np.int32) for k in ("predP", "predA")})
+    rc = lib().orc_trace_cells_2d(ncx, ncz, cn, hx, hz, _p(cid), K, sampling, nc, _p(V), _p(A),
+                                  _p(RX), _p(RZ), _p(st), int(src), int(bool(block)),
+                                  _p(out["tauR"]), _p(out["tauI"]), _p(out["predP"]),
+                                  _p(out["predA"]), _p(out["tstar"]))
+    if rc:
+        raise ValueError(f"orc_trace_cells_2d failed rc={rc}")
     return out

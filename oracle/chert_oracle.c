@@ -639,6 +639,16 @@ static int gcd_int(int a, int b) {
  * half away from zero there -- and an offset in the other half-plane takes
  * the direction opposite to its reverse's, so that an edge and its reverse
  * always read diametrically opposite directions. */
+static int32_t bin_2d(int x, int z, double hx, double hz, int n_dirs) {
+  double dx = x * hx, dz = z * hz;
+  int upper = (x > 0) || (x == 0 && z > 0); /* angle in [0, pi) */
+  double ang = upper ? atan2(dx, dz) : atan2(-dx, -dz); /* from +z to +x */
+  long b = lround(ang * n_dirs / (2.0 * ORC_PI));
+  if (!upper) b = b + n_dirs / 2;
+  b = ((b % n_dirs) + n_dirs) % n_dirs;
+  return (int32_t)b;
+}
+
 int orc_star_2d(int R, double hx, double hz, int n_dirs, int32_t *ox,
                 int32_t *oz, double *L, int32_t *bin) {
   int n = 0;
@@ -651,12 +661,7 @@ int orc_star_2d(int R, double hx, double hz, int n_dirs, int32_t *ox,
         ox[n] = x;
         oz[n] = z;
         L[n] = sqrt(dx * dx + dz * dz);
-        int upper = (x > 0) || (x == 0 && z > 0); /* angle in [0, pi) */
-        double ang = upper ? atan2(dx, dz) : atan2(-dx, -dz); /* from +z to +x */
-        long b = lround(ang * n_dirs / (2.0 * ORC_PI));
-        if (!upper) b = b + n_dirs / 2;
-        b = ((b % n_dirs) + n_dirs) % n_dirs;
-        bin[n] = (int32_t)b;
+        bin[n] = bin_2d(x, z, hx, hz, n_dirs);
       }
       ++n;
     }
@@ -1388,5 +1393,336 @@ int orc_trace_3d(long nx, long ny, long nz, double hx, double hy, double hz,
 out:
   free(ox); free(oy); free(oz); free(bin); free(L); free(col);
   free(t); free(pr); free(hp); free(ord);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O-18  the cell network (grid and nodal ray-network section, eqs 23-24,   */
+/*       27-32): nodes on cell edges, every node pair of a cell an edge,    */
+/*       optionally marched block by block from a heap of cells             */
+/* ------------------------------------------------------------------------ */
+
+/* The network: ncx x ncz rectangular cells, each side divided into cn
+ * intervals of hx (along x) or hz (along z).  Its nodes are the points of
+ * the (ncx cn + 1) x (ncz cn + 1) lattice that lie on a cell edge
+ * (ix % cn == 0 or iz % cn == 0), indexed ix + NX iz like the lattice; the
+ * points inside a cell are not nodes.  Two nodes are joined when both lie on
+ * the boundary of one cell (eq 27: the straight segment between them).  Its
+ * weight follows eqs 28-30 with the classes of its two end nodes: with a
+ * ray-direction cache both ends read the tabulated direction nearest to the
+ * segment (the same rule as for forward-star offsets); with a
+ * slowness-sampled cache each end reads its class's sample whose stored ray
+ * direction has the largest normalised dot product with the segment. */
+typedef struct {
+  long ncx, ncz, NX, NZ;
+  int cn, side;          /* side = 2 cn + 1: offsets (dx, dz) in [-cn, cn]^2 */
+  const int32_t *cls;    /* lattice -> class */
+  long K;
+  int n_cols;
+  const double *V, *A;   /* [K][n_cols] of one mode */
+  const int32_t *st;
+  double *L;             /* [side^2] segment length per offset */
+  int32_t *colR;         /* ray-direction cache: [side^2] column; NULL otherwise */
+  int32_t *best;         /* slowness-sampled cache: [K][side^2]; NULL otherwise */
+} cellnet_t;
+
+static int cell_is_node(const cellnet_t *g, long ix, long iz) {
+  return ix % g->cn == 0 || iz % g->cn == 0;
+}
+
+static int cell_off(const cellnet_t *g, long dx, long dz) {
+  return (int)((dz + g->cn) * g->side + (dx + g->cn));
+}
+
+static double cell_weight(const cellnet_t *g, int field, long i, long j) {
+  long dx = (j % g->NX) - (i % g->NX), dz = (j / g->NX) - (i / g->NX);
+  int o = cell_off(g, dx, dz);
+  long ki = g->cls[i], kj = g->cls[j];
+  int ci, cj;
+  if (g->best) {
+    ci = g->best[ki * g->side * g->side + o];
+    cj = g->best[kj * g->side * g->side + o];
+    if (ci < 0 || cj < 0) return INFINITY;
+  } else {
+    ci = cj = g->colR[o];
+  }
+  const int bad = ORC_ST_NO_BRACKET | ORC_ST_FLUID | ORC_ST_NONPHYS | ORC_ST_NOCONV;
+  if ((g->st[ki * g->n_cols + ci] & bad) || (g->st[kj * g->n_cols + cj] & bad)) return INFINITY;
+  if (field == 0)
+    return g->L[o] / (0.5 * (g->V[ki * g->n_cols + ci] + g->V[kj * g->n_cols + cj]));
+  return g->L[o] * (0.5 * (g->A[ki * g->n_cols + ci] + g->A[kj * g->n_cols + cj]));
+}
+
+/* The cells whose boundary holds lattice node u: up to two columns and two
+ * rows of cells.  Writes cell indices cx + ncx cz into c[], returns count. */
+static int cells_of(const cellnet_t *g, long u, long *c) {
+  long ix = u % g->NX, iz = u / g->NX;
+  long xs[2], zs[2];
+  int nxs = 0, nzs = 0;
+  if (ix % g->cn == 0) {
+    if (ix / g->cn - 1 >= 0) xs[nxs++] = ix / g->cn - 1;
+    if (ix / g->cn < g->ncx) xs[nxs++] = ix / g->cn;
+  } else {
+    xs[nxs++] = ix / g->cn;
+  }
+  if (iz % g->cn == 0) {
+    if (iz / g->cn - 1 >= 0) zs[nzs++] = iz / g->cn - 1;
+    if (iz / g->cn < g->ncz) zs[nzs++] = iz / g->cn;
+  } else {
+    zs[nzs++] = iz / g->cn;
+  }
+  int n = 0;
+  for (int a = 0; a < nxs; ++a)
+    for (int b = 0; b < nzs; ++b) c[n++] = xs[a] + g->ncx * zs[b];
+  return n;
+}
+
+/* The 4 cn boundary nodes of cell c (each once), in any order. */
+static int cell_nodes(const cellnet_t *g, long c, long *v) {
+  long x0 = (c % g->ncx) * g->cn, z0 = (c / g->ncx) * g->cn;
+  int n = 0;
+  for (long dz = 0; dz <= g->cn; ++dz)
+    for (long dx = 0; dx <= g->cn; ++dx)
+      if (dx == 0 || dz == 0 || dx == g->cn || dz == g->cn)
+        v[n++] = (x0 + dx) + g->NX * (z0 + dz);
+  return n;
+}
+
+/* Neighbours of u: the other boundary nodes of every cell holding u (a node
+ * shared by two cells along their common edge is listed twice; the two
+ * copies are the same segment and carry the same weight). */
+static int cell_neighbours(const cellnet_t *g, long u, long *nb) {
+  long cs[4], v[64 * 4];
+  int nc = cells_of(g, u, cs), n = 0;
+  for (int a = 0; a < nc; ++a) {
+    int m = cell_nodes(g, cs[a], v);
+    for (int b = 0; b < m; ++b)
+      if (v[b] != u) nb[n++] = v[b];
+  }
+  return n;
+}
+
+static int cell_dijkstra(const cellnet_t *g, int field, long src, double *tau) {
+  long n = g->NX * g->NZ;
+  for (long i = 0; i < n; ++i) tau[i] = INFINITY;
+  char *done = (char *)calloc((size_t)n, 1);
+  long *nb = (long *)malloc(sizeof(long) * 16 * 64);
+  heap_t h = {0, 0, 0};
+  int rc = 0;
+  if (!done || !nb) { rc = 1; goto out; }
+  tau[src] = 0.0;
+  if (heap_push(&h, 0.0, src)) { rc = 1; goto out; }
+  while (h.n > 0) {
+    heap_item it = heap_pop(&h);
+    long u = it.node;
+    if (done[u] || it.key != tau[u]) continue;
+    done[u] = 1;
+    int m = cell_neighbours(g, u, nb);
+    for (int b = 0; b < m; ++b) {
+      long v = nb[b];
+      if (done[v]) continue;
+      double cand = tau[u] + cell_weight(g, field, u, v);
+      if (cand < tau[v]) {
+        tau[v] = cand;
+        if (heap_push(&h, cand, v)) { rc = 1; goto out; }
+      }
+    }
+  }
+out:
+  free(done);
+  free(nb);
+  free(h.a);
+  return rc;
+}
+
+/* The paper's block marching (eqs 23-24, 31-32): a heap of cells keyed by
+ * their block traveltime T_b = the smallest node traveltime in the cell
+ * (eq 24).  The cell with the smallest key is taken; every ordered pair of
+ * its boundary nodes is relaxed (eq 31 applies both directions of each
+ * segment) until a full pass changes nothing; each neighbouring cell that
+ * shares an improved node is pushed again with its new T_b.  A cell re-enters
+ * the heap whenever one of its nodes improves, so the marching ends at the
+ * network's shortest-path traveltimes (the same fixed point as node
+ * Dijkstra) whatever the order. */
+static int cell_block_march(const cellnet_t *g, int field, long src, double *tau) {
+  long n = g->NX * g->NZ, nc = g->ncx * g->ncz;
+  for (long i = 0; i < n; ++i) tau[i] = INFINITY;
+  double *key = (double *)malloc(sizeof(double) * (size_t)nc);
+  long *v = (long *)malloc(sizeof(long) * 64 * 4);
+  long cs[4];
+  heap_t h = {0, 0, 0};
+  int rc = 0;
+  if (!key || !v) { rc = 1; goto out; }
+  for (long c = 0; c < nc; ++c) key[c] = INFINITY;
+  tau[src] = 0.0;
+  {
+    int k = cells_of(g, src, cs);
+    for (int a = 0; a < k; ++a) {
+      key[cs[a]] = 0.0;
+      if (heap_push(&h, 0.0, cs[a])) { rc = 1; goto out; }
+    }
+  }
+  while (h.n > 0) {
+    heap_item it = heap_pop(&h);
+    long c = it.node;
+    if (it.key != key[c]) continue; /* stale entry */
+    key[c] = INFINITY;              /* taken: re-enters only on a new improvement */
+    int m = cell_nodes(g, c, v);
+    char improved[256] = {0};
+    int changed = 1;
+    while (changed) {
+      changed = 0;
+      for (int a = 0; a < m; ++a) {
+        if (!isfinite(tau[v[a]])) continue;
+        for (int b = 0; b < m; ++b) {
+          if (a == b) continue;
+          double cand = tau[v[a]] + cell_weight(g, field, v[a], v[b]);
+          if (cand < tau[v[b]]) {
+            tau[v[b]] = cand;
+            improved[b] = 1;
+            changed = 1;
+          }
+        }
+      }
+    }
+    for (int b = 0; b < m; ++b) {
+      if (!improved[b]) continue;
+      int k = cells_of(g, v[b], cs);
+      for (int a = 0; a < k; ++a) {
+        long c2 = cs[a];
+        if (c2 == c) continue;
+        /* T_b of the neighbour (eq 24) over its nodes */
+        int m2 = cell_nodes(g, c2, v + 64 * 2);
+        double tb = INFINITY;
+        for (int q = 0; q < m2; ++q)
+          if (tau[v[64 * 2 + q]] < tb) tb = tau[v[64 * 2 + q]];
+        key[c2] = tb;
+        if (heap_push(&h, tb, c2)) { rc = 1; goto out; }
+      }
+    }
+  }
+out:
+  free(key);
+  free(v);
+  free(h.a);
+  return rc;
+}
+
+/* Deterministic predecessors: BFS hop counts over tight segments
+ * (tau_i + w_ij == tau_j), pred_j = the tight neighbour i with the smallest
+ * (hop, node index); t* (field 0 only) folds the attenuation weights along
+ * that tree from the source outwards. */
+static int cell_predecessors(const cellnet_t *g, int field, long src, const double *tau,
+                             int32_t *pred, double *tstar) {
+  long n = g->NX * g->NZ;
+  int32_t *hop = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  long *order = (long *)malloc(sizeof(long) * (size_t)n);
+  long *nb = (long *)malloc(sizeof(long) * 16 * 64);
+  if (!hop || !order || !nb) { free(hop); free(order); free(nb); return 1; }
+  for (long i = 0; i < n; ++i) {
+    pred[i] = -1;
+    hop[i] = -1;
+  }
+  long head = 0, tail = 0;
+  hop[src] = 0;
+  order[tail++] = src;
+  while (head < tail) {
+    long i = order[head++];
+    int m = cell_neighbours(g, i, nb);
+    for (int b = 0; b < m; ++b) {
+      long j = nb[b];
+      if (hop[j] >= 0 || !isfinite(tau[j])) continue;
+      if (tau[i] + cell_weight(g, field, i, j) == tau[j]) {
+        hop[j] = hop[i] + 1;
+        order[tail++] = j;
+      }
+    }
+  }
+  for (long t = 1; t < tail; ++t) {
+    long j = order[t], bi = -1;
+    int m = cell_neighbours(g, j, nb);
+    for (int b = 0; b < m; ++b) {
+      long i = nb[b];
+      if (hop[i] < 0) continue;
+      if (!(tau[i] + cell_weight(g, field, i, j) == tau[j])) continue;
+      if (bi < 0 || hop[i] < hop[bi] || (hop[i] == hop[bi] && i < bi)) bi = i;
+    }
+    pred[j] = (int32_t)bi;
+  }
+  if (tstar) {
+    for (long i = 0; i < n; ++i) tstar[i] = INFINITY;
+    tstar[src] = 0.0;
+    for (long t = 1; t < tail; ++t) {
+      long j = order[t];
+      tstar[j] = tstar[pred[j]] + cell_weight(g, 1, pred[j], j);
+    }
+  }
+  free(hop);
+  free(order);
+  free(nb);
+  return 0;
+}
+
+/* Trace one source on the cell network for one mode.  sampling 0: a
+ * ray-direction cache of n_cols = n_dirs columns; 1: a slowness-sampled cache
+ * of n_cols samples (RX, RZ: stored ray directions).  V, A, RX, RZ, st:
+ * [K][n_cols] slices of the mode.  block != 0 computes the traveltimes with
+ * the block marching instead of node Dijkstra.  Outputs (NULL to skip) are
+ * lattice-sized; points inside cells stay +inf / -1. */
+int orc_trace_cells_2d(long ncx, long ncz, int cn, double hx, double hz,
+                       const int32_t *class_id, long K, int sampling, int n_cols,
+                       const double *V, const double *A, const double *RX, const double *RZ,
+                       const int32_t *st, long src, int block, double *tauR, double *tauI,
+                       int32_t *predP, int32_t *predA, double *tstar) {
+  if (ncx < 1 || ncz < 1 || cn < 1 || cn > 16 || !class_id) return 1;
+  cellnet_t g = {.ncx = ncx, .ncz = ncz, .NX = ncx * cn + 1, .NZ = ncz * cn + 1, .cn = cn,
+                 .side = 2 * cn + 1, .cls = class_id, .K = K, .n_cols = n_cols, .V = V,
+                 .A = A, .st = st};
+  long n = g.NX * g.NZ;
+  if (src < 0 || src >= n || !cell_is_node(&g, src % g.NX, src / g.NX)) return 1;
+  int n_o = g.side * g.side;
+  int32_t *ox = (int32_t *)malloc(sizeof(int32_t) * n_o);
+  int32_t *oz = (int32_t *)malloc(sizeof(int32_t) * n_o);
+  double *t = (double *)malloc(sizeof(double) * (size_t)n);
+  int32_t *p = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  g.L = (double *)malloc(sizeof(double) * n_o);
+  int rc = 0;
+  if (!ox || !oz || !t || !p || !g.L) { rc = 2; goto out; }
+  for (int dz = -cn; dz <= cn; ++dz)
+    for (int dx = -cn; dx <= cn; ++dx) {
+      int o = cell_off(&g, dx, dz);
+      ox[o] = (dx == 0 && dz == 0) ? 1 : dx; /* the centre is never a segment */
+      oz[o] = dz;
+      double ex = ox[o] * hx, ez = oz[o] * hz;
+      g.L[o] = sqrt(ex * ex + ez * ez);
+    }
+  if (sampling == 0) {
+    g.colR = (int32_t *)malloc(sizeof(int32_t) * n_o);
+    if (!g.colR) { rc = 2; goto out; }
+    /* nearest tabulated direction: the forward-star rule applied to the
+     * segment (non-primitive offsets included) */
+    for (int o = 0; o < n_o; ++o) g.colR[o] = bin_2d(ox[o], oz[o], hx, hz, n_cols);
+  } else {
+    g.best = (int32_t *)malloc(sizeof(int32_t) * (size_t)K * n_o);
+    if (!g.best) { rc = 2; goto out; }
+    orc_slow_lookup(K, n_cols, RX, RZ, st, n_o, ox, oz, hx, hz, g.best);
+  }
+  for (int field = 0; field < 2; ++field) {
+    double *out_t = field ? tauI : tauR;
+    int32_t *out_p = field ? predA : predP;
+    double *ts = field ? NULL : tstar;
+    if (!out_t && !out_p && !ts) continue;
+    if (block ? cell_block_march(&g, field, src, t) : cell_dijkstra(&g, field, src, t)) {
+      rc = 2;
+      goto out;
+    }
+    if (out_p || ts) {
+      if (cell_predecessors(&g, field, src, t, p, ts)) { rc = 2; goto out; }
+      if (out_p) memcpy(out_p, p, sizeof(int32_t) * (size_t)n);
+    }
+    if (out_t) memcpy(out_t, t, sizeof(double) * (size_t)n);
+  }
+out:
+  free(ox); free(oz); free(t); free(p); free(g.L); free(g.colR); free(g.best);
   return rc;
 }
