@@ -475,6 +475,62 @@ int chert_trace_graph_finish(chert_trace_graph *g, void *stream,
                              chert_trace_stats *stats_host);
 int chert_trace_graph_destroy(chert_trace_graph *g);
 
+/* ------------------------------------------------------------------------
+ * The cell network (grid and nodal ray-network section; eqs 23-24, 27-32).
+ * The medium is cut into ncx x ncz rectangular cells whose sides hold
+ * cell_n intervals of hx (along x) or hz (along z).  The nodes are the
+ * points of the NX x NZ lattice (NX = ncx cell_n + 1, NZ = ncz cell_n + 1)
+ * that lie on a cell edge (ix % cell_n == 0 or iz % cell_n == 0), indexed
+ * ix + NX iz; points inside a cell are not nodes.  Every pair of nodes on the
+ * boundary of one cell is joined by the straight segment between them
+ * (eq 27); its weight is eqs 28-30 with the classes of its two end nodes:
+ * a ray-direction cache is read at the tabulated direction nearest to the
+ * segment (the forward star's rule, non-primitive offsets included), a
+ * slowness-sampled cache at each end class's closest stored ray direction.
+ * Each traveltime field is the network's shortest-path field, relaxed in
+ * both directions of each segment (eq 31) cell by cell; with
+ * o->bucket_width > 0 the cells are taken in order of their block
+ * traveltime (eqs 23-24, 32) within that width (units of the smallest
+ * positive segment weight of the field), else every woken cell each round.
+ * Predecessors: BFS hop counts over tight segments (tau_i + w_ij == tau_j),
+ * pred_j = the tight neighbour with the smallest (hop, node index); t* folds
+ * the attenuation weights along the propagation tree.
+ * ---------------------------------------------------------------------- */
+typedef struct chert_cell_grid {
+  int32_t ncx, ncz;   /* cells along x and z (>= 1)                       */
+  int32_t cell_n;     /* intervals per cell side, 1..16 (4 cell_n <= 64)  */
+  int32_t reserved;   /* 0                                               */
+  double hx, hz;      /* lattice spacing along x and z [m]               */
+  const int32_t *class_id_dev; /* [NZ][NX] class of every lattice point
+                         (read at nodes only; required)                   */
+} chert_cell_grid;
+
+/* Workspace of chert_trace_cells (0 on invalid arguments). */
+size_t chert_trace_cells_workspace_bytes(const chert_cache_desc *d, int64_t n_classes,
+                                         const chert_cell_grid *g, int32_t n_src,
+                                         const chert_trace_opts *o);
+
+/* Trace n_src sources (lattice indices of nodes) of one mode on the cell
+ * network of g with a 2D class cache (ray-direction or slowness-sampled,
+ * any subset holding every segment bin).  Outputs are device arrays
+ * [n_src][NX NZ] under the same output-mask rules as chert_trace_field;
+ * lattice points inside cells get +inf (tau, t*) and -1 (pred).  Options
+ * read: outputs, max_rounds, bucket_width, stats_host (rounds[0] =
+ * traveltime rounds, rounds[1] = BFS levels launched, tile_visits[0] = cell
+ * visits, edge_relaxations[0] = pair relaxations, levels_sum[0] = passes
+ * over the pairs of the visited cells), abort_flag_host; the tile fields and
+ * launch are ignored.  INVALID_ARG on a source inside a cell, a class id out
+ * of range (checked on the device before any output is written) or a
+ * workspace that is too small or not 256-byte aligned.  Synchronous with
+ * respect to `stream` (the host checks the rounds); NO_CONVERGENCE when the
+ * round cap is reached. */
+int chert_trace_cells(const chert_cache_desc *d, const void *cache_dev, int64_t n_classes,
+                      const chert_cell_grid *g, int32_t mode, const int64_t *src_nodes_host,
+                      int32_t n_src, const chert_trace_opts *o, double *tau_r_dev,
+                      double *tau_i_dev, double *tstar_dev, int32_t *pred_p_dev,
+                      int32_t *pred_a_dev, void *workspace_dev, size_t workspace_bytes,
+                      void *stream);
+
 /* Raypath (eqs 25, 33-34): follow pred from rcv back to src and write the
  * node sequence src ... rcv into path_out.  Host, synchronous.
  * *path_len receives the length (also on CAPACITY, so the caller can retry).

@@ -45,6 +45,7 @@ EXPORTS = (
     "chert_trace_graph_create", "chert_trace_graph_launch", "chert_trace_graph_finish",
     "chert_trace_graph_destroy", "chert_trace_autotune_workspace_bytes", "chert_trace_autotune",
     "chert_star_3d", "chert_build_cache_noalloc", "chert_build_cache_noalloc_max_bytes",
+    "chert_trace_cells_workspace_bytes", "chert_trace_cells",
 )
 WARM_NSTATS = 10
 # parameter blocks of the surrogate, in their order in the parameter vector
@@ -103,6 +104,12 @@ class Grid(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("radius", ctypes.c_int32),
                 ("nx", ctypes.c_int64), ("nz", ctypes.c_int64), ("ny", ctypes.c_int64),
                 ("hx", ctypes.c_double), ("hz", ctypes.c_double), ("hy", ctypes.c_double),
+                ("class_id_dev", ctypes.c_void_p)]
+
+
+class CellGrid(ctypes.Structure):
+    _fields_ = [("ncx", ctypes.c_int32), ("ncz", ctypes.c_int32), ("cell_n", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("hx", ctypes.c_double), ("hz", ctypes.c_double),
                 ("class_id_dev", ctypes.c_void_p)]
 
 
@@ -206,6 +213,9 @@ def lib():
         L.chert_trace_autotune_workspace_bytes.restype = sz
         L.chert_trace_autotune.argtypes = [P, i32, P, P, sz, P, P]
         L.chert_star_3d.argtypes = [i32, d, d, d, i32, P, P, P, P, P]
+        L.chert_trace_cells_workspace_bytes.argtypes = [P, i64, P, i32, P]
+        L.chert_trace_cells_workspace_bytes.restype = sz
+        L.chert_trace_cells.argtypes = [P, P, i64, P, i32, P, i32, P, P, P, P, P, P, P, sz, P]
         _lib = L
     return _lib
 
@@ -412,6 +422,31 @@ def chert_prof_read():
 def chert_trace_workspace_bytes(desc, n_classes, grid, n_src, opts):
     return int(lib().chert_trace_workspace_bytes(ctypes.byref(desc), n_classes,
                                                  ctypes.byref(grid), n_src, ctypes.byref(opts)))
+
+
+def make_cell_grid(ncx, ncz, cell_n, hx, hz, class_id_dev):
+    """Cell network: ncx x ncz cells of cell_n intervals per side; the class
+    map covers the (ncz cell_n + 1) x (ncx cell_n + 1) lattice."""
+    g = CellGrid(ncx, ncz, cell_n, 0, hx, hz, class_id_dev.data_ptr())
+    g._keep = class_id_dev
+    return g
+
+
+def chert_trace_cells_workspace_bytes(desc, n_classes, grid, n_src, opts):
+    return int(lib().chert_trace_cells_workspace_bytes(ctypes.byref(desc), n_classes,
+                                                       ctypes.byref(grid), n_src,
+                                                       ctypes.byref(opts)))
+
+
+def chert_trace_cells(desc, cache_dev, n_classes, grid, mode, src_nodes: Sequence[int], opts,
+                      tau_r=None, tau_i=None, tstar=None, pred_p=None, pred_a=None,
+                      workspace_dev=None, stream=None):
+    src = np.ascontiguousarray(np.asarray(src_nodes, dtype=np.int64).reshape(-1))
+    ws = workspace_dev.numel() * workspace_dev.element_size() if workspace_dev is not None else 0
+    _check(lib().chert_trace_cells(
+        ctypes.byref(desc), _ptr(cache_dev), n_classes, ctypes.byref(grid), mode,
+        src.ctypes.data, int(src.size), ctypes.byref(opts), _ptr(tau_r), _ptr(tau_i),
+        _ptr(tstar), _ptr(pred_p), _ptr(pred_a), _ptr(workspace_dev), ws, _stream(stream)))
 
 
 def chert_trace_field(desc, cache_dev, n_classes, grid, mode, src_nodes: Sequence[int], opts,

@@ -3,8 +3,9 @@
 Per-file floating-point contraction:
   - cache_build.hip: FMA contraction allowed (the local solve is compared
     with a tolerance);
-  - trace.hip, frontier.hip, tile3d.hip, abi_host.cpp: -ffp-contract=off, so edge weights, traveltime
-    sums and the host-side star lengths are plain IEEE operations.
+  - trace.hip, frontier.hip, tile3d.hip, cellnet.hip, abi_host.cpp:
+    -ffp-contract=off, so edge weights, traveltime sums and the host-side
+    star and segment lengths are plain IEEE operations.
 """
 from __future__ import annotations
 
@@ -27,6 +28,7 @@ SOURCES = [
     ("trace.hip", ["-ffp-contract=off"]),
     ("frontier.hip", ["-ffp-contract=off"]),
     ("tile3d.hip", ["-ffp-contract=off"]),
+    ("cellnet.hip", ["-ffp-contract=off"]),
     ("surrogate.hip", ["-ffp-contract=fast"]),
     ("abi_host.cpp", ["-ffp-contract=off", "-x", "hip"]),
 ]

@@ -38,7 +38,7 @@ static int gcd_i(int a, int b) {
 // direction angle in [0, pi) (ox > 0, or ox == 0 and oz > 0); the reversed
 // offset takes the diametrically opposite bin, so bin(-o) = bin(o) + n_dirs/2
 // also where the angle falls exactly between two tabulated directions.
-static int32_t star_bin_2d(int x, int z, double hx, double hz, int n_dirs) {
+int32_t star_bin_2d(int x, int z, double hx, double hz, int n_dirs) {
   const bool canon = x > 0 || (x == 0 && z > 0);
   const double dx = (canon ? x : -x) * hx, dz = (canon ? z : -z) * hz;
   long b = lround(atan2(dx, dz) * n_dirs / (2.0 * M_PI));

@@ -1,0 +1,718 @@
+// The cell network of the grid and nodal ray-network section (eqs 23-24,
+// 27-32) on gfx950: nodes on the edges of rectangular cells, every pair of
+// boundary nodes of a cell joined by a straight segment, the traveltimes
+// marched cell by cell.
+//
+// Traveltimes: one wave per (problem, cell) visit, one lane per boundary node
+// (4 cn <= 64).  The wave loads its cell's traveltimes and classes once,
+// then relaxes every ordered pair (eq 31) from lane broadcasts until a pass
+// changes nothing (Jacobi passes inside the cell), and lowers the improved
+// nodes in HBM with a 64-bit atomicMin on the traveltime bits (traveltimes
+// are >= 0, so their bit patterns order like the values).  A cell is woken
+// with key = the smallest improved traveltime among its nodes (the block
+// traveltime of eq 24 over what changed); with an ordering width each round
+// takes only the woken cells whose key is within the width of its problem's
+// smallest key (the heap of cells of eqs 23 and 32 widened to a bucket, so a
+// round holds many cells).  The fixed point is the network's shortest-path
+// traveltimes whatever the schedule.
+//
+// Predecessors and t*: level-synchronous BFS over tight segments
+// (tau_i + w_ij == tau_j) from the source, one wave per node of the current
+// level, lanes over the boundary nodes of the node's cells: pred_j = the
+// tight neighbour one level up with the smallest node index (the smallest
+// (hop, index) among all tight neighbours), t*_j = t*_pred + the attenuation
+// weight of that segment, each parent's value final one level earlier.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "chert_internal.h"
+
+namespace chert {
+namespace {
+
+constexpr int kCellMaxN = 16;  // 4 cn boundary nodes <= 64 lanes
+constexpr int kCellWaves = 4;  // waves per workgroup
+constexpr int kCellThreads = 64 * kCellWaves;
+constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+__device__ __forceinline__ unsigned long long dbits(double x) {
+  return (unsigned long long)__double_as_longlong(x);
+}
+
+__device__ __forceinline__ double bcast_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// boundary slot s of a cell of side cn -> local lattice point (lx, lz):
+// top edge left to right, right edge downwards, bottom edge right to left,
+// left edge upwards; each boundary point once
+__device__ __forceinline__ void slot_xy(int s, int cn, int& lx, int& lz) {
+  const int e = s / cn, r = s - e * cn;
+  if (e == 0) {
+    lx = r;
+    lz = 0;
+  } else if (e == 1) {
+    lx = cn;
+    lz = r;
+  } else if (e == 2) {
+    lx = cn - r;
+    lz = cn;
+  } else {
+    lx = 0;
+    lz = cn - r;
+  }
+}
+
+// the cells whose boundary holds lattice point (gx, gz) (a node), at most 4
+__device__ __forceinline__ int cells_of(int gx, int gz, int cn, int ncx, int ncz, int* cs) {
+  int xs[2], zs[2], nx = 0, nz = 0;
+  const int qx = gx / cn, qz = gz / cn;
+  if (gx - qx * cn == 0) {
+    if (qx - 1 >= 0) xs[nx++] = qx - 1;
+    if (qx < ncx) xs[nx++] = qx;
+  } else {
+    xs[nx++] = qx;
+  }
+  if (gz - qz * cn == 0) {
+    if (qz - 1 >= 0) zs[nz++] = qz - 1;
+    if (qz < ncz) zs[nz++] = qz;
+  } else {
+    zs[nz++] = qz;
+  }
+  int n = 0;
+  for (int a = 0; a < nx; ++a)
+    for (int b = 0; b < nz; ++b) cs[n++] = xs[a] + ncx * zs[b];
+  return n;
+}
+
+struct CellArgs {
+  int ncx, ncz, cn, side, NX, K, n_src, n_prob;
+  int64_t n, C;
+  const int32_t* cls;  // lattice -> class
+  const double* W;     // [2][K][K][side^2]
+  double* tau[2];      // per field slot: rows [n_src][n]
+  int field_of[2];     // field slot -> 0 (propagation) or 1 (attenuation)
+  const int64_t* src;  // [n_src]
+  int32_t* active;     // [P][C]
+  unsigned long long* key;     // [P][C]
+  unsigned long long* minkey;  // [2][P] (round parity)
+  int32_t* list;               // [P C] selected (problem, cell) items
+  int32_t* count;              // [2] (round parity)
+  unsigned long long* stats;   // visits, pair relaxations, passes
+  const double* wmin;          // [2]
+  double bucket;               // ordering width in units of wmin (0: none)
+  // level phase
+  int32_t* hop;        // [P][n]
+  int32_t* bfs;        // [P][n] BFS order
+  int32_t* lvl;        // [3][P]: start, end, tail
+  int32_t* alive;      // nodes added since the host last looked
+  int32_t* pred[2];    // per field slot, rows [n_src][n] (nullable)
+  double* tstar;       // rows [n_src][n] for the propagation slot (nullable)
+  int tree_mask;       // bit fi: problems of field slot fi need the tree
+};
+
+__device__ __forceinline__ double* tau_row(const CellArgs& a, int p) {
+  const int fi = p / a.n_src, s = p - fi * a.n_src;
+  return a.tau[fi] + (int64_t)s * a.n;
+}
+
+// fill the outputs: +inf traveltimes and t*, -1 predecessors and hops
+__global__ void k_cell_fill(CellArgs a) {
+  const int p = blockIdx.y;
+  const int fi = p / a.n_src, s = p - fi * a.n_src;
+  double* t = a.tau[fi] + (int64_t)s * a.n;
+  int32_t* pr = a.pred[fi] ? a.pred[fi] + (int64_t)s * a.n : nullptr;
+  double* ts = (a.tstar && a.field_of[fi] == 0) ? a.tstar + (int64_t)s * a.n : nullptr;
+  int32_t* hp = a.hop + (int64_t)p * a.n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    t[i] = INFINITY;
+    hp[i] = -1;
+    if (pr) pr[i] = -1;
+    if (ts) ts[i] = INFINITY;
+  }
+  int32_t* act = a.active + (int64_t)p * a.C;
+  unsigned long long* ky = a.key + (int64_t)p * a.C;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.C;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    act[c] = 0;
+    ky[c] = kInfBits;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.minkey[p] = kInfBits;
+    a.minkey[a.n_prob + p] = kInfBits;
+  }
+  if (p == 0 && blockIdx.x == 0 && threadIdx.x < 8) {
+    if (threadIdx.x < 2) a.count[threadIdx.x] = 0;
+    if (threadIdx.x < 3) a.stats[threadIdx.x] = 0;
+    if (threadIdx.x == 3) *a.alive = 0;
+  }
+}
+
+// the source: tau = 0, its cells woken with key 0; the level phase seeded
+__global__ void k_cell_seed(CellArgs a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n_prob) return;
+  const int fi = p / a.n_src, s = p - fi * a.n_src;
+  const int64_t src = a.src[s];
+  tau_row(a, p)[src] = 0.0;
+  int cs[4];
+  const int nc = cells_of((int)(src % a.NX), (int)(src / a.NX), a.cn, a.ncx, a.ncz, cs);
+  for (int q = 0; q < nc; ++q) {
+    a.active[(int64_t)p * a.C + cs[q]] = 1;
+    a.key[(int64_t)p * a.C + cs[q]] = 0ull;
+  }
+  int32_t* lv = a.lvl;
+  if ((a.tree_mask >> fi) & 1) {
+    a.hop[(int64_t)p * a.n + src] = 0;
+    a.bfs[(int64_t)p * a.n] = (int32_t)src;
+    lv[p] = 0;                   // start
+    lv[a.n_prob + p] = 1;        // end
+    lv[2 * a.n_prob + p] = 1;    // tail
+    if (a.tstar && a.field_of[fi] == 0) a.tstar[(int64_t)s * a.n + src] = 0.0;
+  } else {
+    lv[p] = lv[a.n_prob + p] = lv[2 * a.n_prob + p] = 0;
+  }
+}
+
+// round r, step 1 (ordered rounds only): each problem's smallest key
+__global__ void k_cell_minkey(CellArgs a, int r) {
+  const int64_t total = (int64_t)a.n_prob * a.C;
+  unsigned long long* mk = a.minkey + (int64_t)(r & 1) * a.n_prob;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    if (!a.active[t]) continue;
+    const int p = (int)(t / a.C);
+    const unsigned long long k = a.key[t];
+    if (k < mk[p]) atomicMin(&mk[p], k);
+  }
+}
+
+// round r, step 2: take the woken cells (within the width of the smallest
+// key when ordered) into this round's list; reset the other parity's slots
+__global__ void k_cell_select(CellArgs a, int r) {
+  const int64_t total = (int64_t)a.n_prob * a.C;
+  const unsigned long long* mk = a.minkey + (int64_t)(r & 1) * a.n_prob;
+  int32_t* cnt = a.count + (r & 1);
+  const int lane = __lane_id();
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total;
+       base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = base + threadIdx.x;
+    bool take = false;
+    if (t < total && a.active[t]) {
+      take = true;
+      if (a.bucket > 0.0) {
+        const int p = (int)(t / a.C);
+        const int f = a.field_of[p / a.n_src];
+        const double lim = __longlong_as_double((long long)mk[p]) + a.bucket * a.wmin[f];
+        take = __longlong_as_double((long long)a.key[t]) <= lim;
+      }
+    }
+    const unsigned long long m = __ballot(take);
+    if (m) {
+      int pos0 = 0;
+      const int leader = __ffsll((long long)m) - 1;
+      if (lane == leader) pos0 = atomicAdd(cnt, __popcll(m));
+      pos0 = __shfl(pos0, leader);
+      if (take) {
+        const int rank = __popcll(m & ((1ull << lane) - 1ull));
+        a.list[pos0 + rank] = (int32_t)t;
+        a.active[t] = 0;
+        a.key[t] = kInfBits;
+      }
+    }
+  }
+  // the next round's counter and minima start afresh (this round's relax
+  // reads only this parity; the previous round's relax has finished)
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) a.count[(r + 1) & 1] = 0;
+    unsigned long long* nm = a.minkey + (int64_t)((r + 1) & 1) * a.n_prob;
+    for (int p = threadIdx.x; p < a.n_prob; p += blockDim.x) nm[p] = kInfBits;
+  }
+}
+
+// round r, step 3: relax the listed cells
+__global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) {
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * kCellWaves + (threadIdx.x >> 6);
+  const int nw = gridDim.x * kCellWaves;
+  const int count = a.count[r & 1];
+  const int cn = a.cn, ns = 4 * cn, side = a.side, K = a.K;
+  const int64_t s2 = (int64_t)side * side;
+  int lx = 0, lz = 0;
+  if (lane < ns) slot_xy(lane, cn, lx, lz);
+  unsigned long long visits = 0, pairs = 0, passes_all = 0;
+  for (int it = wave; it < count; it += nw) {
+    const int64_t item = a.list[it];
+    const int p = (int)(item / a.C);
+    const int c = (int)(item - (int64_t)p * a.C);
+    const int cx = c % a.ncx, cz = c / a.ncx;
+    double* tau = tau_row(a, p);
+    const double* W = a.W + (int64_t)a.field_of[p / a.n_src] * K * K * s2;
+    const int gx = cx * cn + lx, gz = cz * cn + lz;
+    const int64_t node = (int64_t)gx + (int64_t)a.NX * gz;
+    int k = 0;
+    double t = INFINITY;
+    if (lane < ns) {
+      k = a.cls[node];
+      t = tau[node];
+    }
+    const double t0 = t;
+    int passes = 0;
+    for (;;) {
+      double best = t;
+      for (int s = 0; s < ns; ++s) {
+        const double ta = bcast_d(t, s);
+        if (!(ta < INFINITY)) continue;  // uniform: no path into slot s yet
+        const int ka = __builtin_amdgcn_readlane(k, s);
+        int ax, az;
+        slot_xy(s, cn, ax, az);
+        if (lane < ns && lane != s) {
+          const int off = (lz - az + cn) * side + (lx - ax + cn);
+          const double cand = ta + W[((int64_t)ka * K + k) * s2 + off];
+          if (cand < best) best = cand;
+        }
+      }
+      ++passes;
+      const bool ch = best < t;
+      t = best;
+      if (!__ballot(ch)) break;
+    }
+    ++visits;
+    pairs += (unsigned long long)passes * ns * (ns - 1);
+    passes_all += passes;
+    if (lane < ns && t < t0) {
+      const unsigned long long nb = dbits(t);
+      const unsigned long long old = atomicMin((unsigned long long*)&tau[node], nb);
+      if (nb < old) {  // wake the node's other cells
+        int cs[4];
+        const int nc = cells_of(gx, gz, cn, a.ncx, a.ncz, cs);
+        for (int q = 0; q < nc; ++q) {
+          if (cs[q] == c) continue;
+          const int64_t e = (int64_t)p * a.C + cs[q];
+          atomicMin(&a.key[e], nb);
+          a.active[e] = 1;
+        }
+      }
+    }
+  }
+  if (lane == 0 && visits) {
+    atomicAdd(&a.stats[0], visits);
+    atomicAdd(&a.stats[1], pairs);
+    atomicAdd(&a.stats[2], passes_all);
+  }
+}
+
+// level L of the BFS over tight segments: grid (x, problem); one wave per
+// node j of the level.  Lanes walk the boundary nodes v of j's cells:
+// pred_j = the smallest v one level up with tau_v + w(v->j) == tau_j;
+// every v not yet reached with tau_j + w(j->v) == tau_v joins level L+1
+// (one winner per node through a compare-and-swap on its hop).
+__global__ void __launch_bounds__(kCellThreads) k_cell_level(CellArgs a, int L) {
+  const int p = blockIdx.y;
+  const int fi = p / a.n_src, s = p - fi * a.n_src;
+  if (!((a.tree_mask >> fi) & 1)) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * kCellWaves + (threadIdx.x >> 6);
+  const int nw = gridDim.x * kCellWaves;
+  const int start = a.lvl[p], end = a.lvl[a.n_prob + p];
+  const int cn = a.cn, ns = 4 * cn, side = a.side, K = a.K;
+  const int64_t s2 = (int64_t)side * side;
+  const int f = a.field_of[fi];
+  const double* W = a.W + (int64_t)f * K * K * s2;
+  const double* tau = a.tau[fi] + (int64_t)s * a.n;
+  int32_t* hop = a.hop + (int64_t)p * a.n;
+  int32_t* bfs = a.bfs + (int64_t)p * a.n;
+  int32_t* tail = a.lvl + 2 * a.n_prob + p;
+  int lx = 0, lz = 0;
+  if (lane < ns) slot_xy(lane, cn, lx, lz);
+  int added = 0;
+  for (int idx = start + wave; idx < end; idx += nw) {
+    const int64_t j = bfs[idx];
+    const int jx = (int)(j % a.NX), jz = (int)(j / a.NX);
+    const double tj = tau[j];
+    const int kj = a.cls[j];
+    int cs[4];
+    const int nc = cells_of(jx, jz, cn, a.ncx, a.ncz, cs);
+    int best = 0x7fffffff;
+    for (int q = 0; q < nc; ++q) {
+      const int vx = (cs[q] % a.ncx) * cn + lx, vz = (cs[q] / a.ncx) * cn + lz;
+      const int64_t v = (int64_t)vx + (int64_t)a.NX * vz;
+      if (lane >= ns || v == j) continue;
+      const int kv = a.cls[v];
+      const double tv = tau[v];
+      const int hv = hop[v];
+      if (L > 0 && hv == L - 1) {  // v -> j tight?
+        const int off = (jz - vz + cn) * side + (jx - vx + cn);
+        if (tv + W[((int64_t)kv * K + kj) * s2 + off] == tj && (int)v < best) best = (int)v;
+      }
+      if (hv == -1 && tv < INFINITY) {  // j -> v tight?
+        const int off = (vz - jz + cn) * side + (vx - jx + cn);
+        if (tj + W[((int64_t)kj * K + kv) * s2 + off] == tv &&
+            atomicCAS(&hop[v], -1, L + 1) == -1) {
+          bfs[atomicAdd(tail, 1)] = (int32_t)v;
+          ++added;
+        }
+      }
+    }
+    if (L > 0) {
+      for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o));
+      // a node of level L always has a tight neighbour one level up (the
+      // one that reached it); the check only keeps the reads in bounds
+      if (lane == 0 && best != 0x7fffffff) {
+        if (a.pred[fi]) a.pred[fi][(int64_t)s * a.n + j] = best;
+        if (a.tstar && f == 0) {
+          const int64_t i = best;
+          const int ix = (int)(i % a.NX), iz = (int)(i / a.NX);
+          const int off = (jz - iz + cn) * side + (jx - ix + cn);
+          const double wI = a.W[(int64_t)K * K * s2 + ((int64_t)a.cls[i] * K + kj) * s2 + off];
+          a.tstar[(int64_t)s * a.n + j] = a.tstar[(int64_t)s * a.n + i] + wI;
+        }
+      }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) added += __shfl_xor(added, o);
+  if (lane == 0 && added) atomicAdd(a.alive, added);
+}
+
+// close level L: the nodes added during it form the next level
+__global__ void k_cell_level_advance(CellArgs a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n_prob) return;
+  a.lvl[p] = a.lvl[a.n_prob + p];
+  a.lvl[a.n_prob + p] = a.lvl[2 * a.n_prob + p];
+}
+
+__global__ void k_cell_zero(int32_t* x) { *x = 0; }
+
+// ---------------------------------------------------------------- plan ----
+
+struct CellPlan {
+  int cn = 0, side = 0, NX = 0, NZ = 0, n_prob = 0, nfs = 0, max_rounds = 0, n_cols = 0;
+  int64_t n = 0, C = 0, K = 0;
+  int fields[2] = {0, 0};
+  bool slow = false;
+  size_t off_tab = 0, off_W = 0, off_best = 0, off_ctl = 0, off_src = 0, off_act = 0,
+         off_key = 0, off_list = 0, off_hop = 0, off_bfs = 0, off_lvl = 0, total = 0;
+};
+
+int cell_plan(const chert_cache_desc* d, int64_t n_classes, const chert_cell_grid* g,
+              int32_t mode, const int64_t* src, int32_t n_src, const chert_trace_opts* o,
+              CellPlan* P) {
+  if (!d || !g || !o) return fail(CHERT_ERR_INVALID_ARG, "null descriptor, grid or options");
+  chert_cache_layout lay;
+  int rc = chert_cache_layout_of(d, n_classes, &lay);
+  if (rc) return rc;
+  if (d->dim != 2) return fail(CHERT_ERR_INVALID_ARG, "cell networks are 2D");
+  if (mode < 0 || mode > 2 || !(d->mode_mask & (1u << mode)))
+    return fail(CHERT_ERR_INVALID_ARG, "mode not in the cache");
+  if (g->ncx < 1 || g->ncz < 1) return fail(CHERT_ERR_INVALID_ARG, "need at least one cell");
+  if (g->cell_n < 1 || g->cell_n > kCellMaxN)
+    return fail(CHERT_ERR_INVALID_ARG, "cell_n must be 1..16");
+  if (!(g->hx > 0.0) || !(g->hz > 0.0) || !isfinite(g->hx) || !isfinite(g->hz))
+    return fail(CHERT_ERR_INVALID_ARG, "spacing must be positive and finite");
+  if (!g->class_id_dev) return fail(CHERT_ERR_INVALID_ARG, "cell networks need a class map");
+  P->cn = g->cell_n;
+  P->side = 2 * P->cn + 1;
+  const int64_t NX = (int64_t)g->ncx * P->cn + 1, NZ = (int64_t)g->ncz * P->cn + 1;
+  if (NX * NZ >= 0x7fffffffLL) return fail(CHERT_ERR_INVALID_ARG, "lattice too large");
+  P->NX = (int)NX;
+  P->NZ = (int)NZ;
+  P->n = NX * NZ;
+  P->C = (int64_t)g->ncx * g->ncz;
+  P->K = n_classes;
+  if (n_classes < 1) return fail(CHERT_ERR_INVALID_ARG, "need at least one class");
+  if (n_classes * n_classes * P->side * P->side >= 0x7fffffffLL)
+    return fail(CHERT_ERR_UNSUPPORTED, "class-pair table too large");
+  P->slow = d->sampling == CHERT_SAMPLE_SLOWNESS;
+  P->n_cols = d->n_subset ? d->n_subset : d->n_dirs;
+  const uint32_t outs = o->outputs;
+  if (outs == 0 || (outs & ~31u) || !(outs & (CHERT_OUT_TAU_R | CHERT_OUT_TAU_I)))
+    return fail(CHERT_ERR_INVALID_ARG, "bad output mask");
+  if ((outs & CHERT_OUT_TSTAR) && !((outs & CHERT_OUT_TAU_R) && (outs & CHERT_OUT_PRED_P)))
+    return fail(CHERT_ERR_INVALID_ARG, "TSTAR needs TAU_R and PRED_P");
+  if ((outs & CHERT_OUT_PRED_P) && !(outs & CHERT_OUT_TAU_R))
+    return fail(CHERT_ERR_INVALID_ARG, "PRED_P needs TAU_R");
+  if ((outs & CHERT_OUT_PRED_A) && !(outs & CHERT_OUT_TAU_I))
+    return fail(CHERT_ERR_INVALID_ARG, "PRED_A needs TAU_I");
+  if (!(o->bucket_width >= 0.0) || !isfinite(o->bucket_width))
+    return fail(CHERT_ERR_INVALID_ARG, "bucket_width must be finite and >= 0");
+  if (n_src < 1 || !src) return fail(CHERT_ERR_INVALID_ARG, "need sources");
+  for (int i = 0; i < n_src; ++i) {
+    if (src[i] < 0 || src[i] >= P->n) return fail(CHERT_ERR_INVALID_ARG, "source out of range");
+    const int64_t x = src[i] % NX, z = src[i] / NX;
+    if (x % P->cn != 0 && z % P->cn != 0)
+      return fail(CHERT_ERR_INVALID_ARG, "a source inside a cell is not a node");
+  }
+  P->nfs = 0;
+  if (outs & CHERT_OUT_TAU_R) P->fields[P->nfs++] = 0;
+  if (outs & CHERT_OUT_TAU_I) P->fields[P->nfs++] = 1;
+  if ((int64_t)P->nfs * n_src > 65535) return fail(CHERT_ERR_UNSUPPORTED, "too many sources");
+  P->n_prob = P->nfs * n_src;
+  if ((int64_t)P->n_prob * P->C >= 0x7fffffffLL || (int64_t)P->n_prob * P->n >= (1LL << 40))
+    return fail(CHERT_ERR_UNSUPPORTED, "batch too large for one call");
+  P->max_rounds = o->max_rounds > 0 ? o->max_rounds : 4096 + 64 * (g->ncx + g->ncz);
+  const int s2 = P->side * P->side;
+  size_t off = 0;
+  P->off_tab = off;  // L (double), then ox, oz, col (int32)
+  off += al256((size_t)s2 * (3 * sizeof(int32_t) + sizeof(double)));
+  P->off_W = off;
+  off += al256((size_t)2 * n_classes * n_classes * s2 * sizeof(double));
+  P->off_best = off;
+  if (P->slow) off += al256((size_t)n_classes * s2 * sizeof(int32_t));
+  P->off_ctl = off;  // count[2], err, alive, stats[3], wmin[2], minkey[2][P], lvl[3][P]
+  off += al256(256 + (size_t)2 * P->n_prob * sizeof(unsigned long long));
+  P->off_lvl = off;
+  off += al256((size_t)3 * P->n_prob * sizeof(int32_t));
+  P->off_src = off;
+  off += al256((size_t)n_src * sizeof(int64_t));
+  P->off_act = off;
+  off += al256((size_t)P->n_prob * P->C * sizeof(int32_t));
+  P->off_key = off;
+  off += al256((size_t)P->n_prob * P->C * sizeof(unsigned long long));
+  P->off_list = off;
+  off += al256((size_t)P->n_prob * P->C * sizeof(int32_t));
+  P->off_hop = off;
+  off += al256((size_t)P->n_prob * P->n * sizeof(int32_t));
+  P->off_bfs = off;
+  off += al256((size_t)P->n_prob * P->n * sizeof(int32_t));
+  P->total = off;
+  return CHERT_OK;
+}
+
+}  // namespace
+}  // namespace chert
+
+using namespace chert;
+
+extern "C" size_t chert_trace_cells_workspace_bytes(const chert_cache_desc* d,
+                                                    int64_t n_classes,
+                                                    const chert_cell_grid* g, int32_t n_src,
+                                                    const chert_trace_opts* o) {
+  if (!g || n_src < 1) return 0;
+  // sources are checked by the trace call; a lattice corner stands in here
+  std::vector<int64_t> src((size_t)n_src, 0);
+  CellPlan P;
+  if (cell_plan(d, n_classes, g, 0, src.data(), n_src, o, &P)) {
+    // the mode is checked by the trace call: retry with any cached mode
+    for (int m = 1; m < 3; ++m)
+      if (d && (d->mode_mask & (1u << m)) &&
+          cell_plan(d, n_classes, g, m, src.data(), n_src, o, &P) == CHERT_OK)
+        return P.total;
+    return 0;
+  }
+  return P.total;
+}
+
+extern "C" int chert_trace_cells(const chert_cache_desc* d, const void* cache_dev,
+                                 int64_t n_classes, const chert_cell_grid* g, int32_t mode,
+                                 const int64_t* src_nodes_host, int32_t n_src,
+                                 const chert_trace_opts* o, double* tau_r_dev, double* tau_i_dev,
+                                 double* tstar_dev, int32_t* pred_p_dev, int32_t* pred_a_dev,
+                                 void* workspace_dev, size_t workspace_bytes, void* stream) {
+  CellPlan P;
+  int rc = cell_plan(d, n_classes, g, mode, src_nodes_host, n_src, o, &P);
+  if (rc) return rc;
+  const uint32_t outs = o->outputs;
+  if (!cache_dev) return fail(CHERT_ERR_INVALID_ARG, "null cache");
+  if ((outs & CHERT_OUT_TAU_R) && !tau_r_dev) return fail(CHERT_ERR_INVALID_ARG, "null tau_r");
+  if ((outs & CHERT_OUT_TAU_I) && !tau_i_dev) return fail(CHERT_ERR_INVALID_ARG, "null tau_i");
+  if ((outs & CHERT_OUT_TSTAR) && !tstar_dev) return fail(CHERT_ERR_INVALID_ARG, "null tstar");
+  if ((outs & CHERT_OUT_PRED_P) && !pred_p_dev) return fail(CHERT_ERR_INVALID_ARG, "null pred_p");
+  if ((outs & CHERT_OUT_PRED_A) && !pred_a_dev) return fail(CHERT_ERR_INVALID_ARG, "null pred_a");
+  if (!workspace_dev || workspace_bytes < P.total || ((uintptr_t)workspace_dev & 255u))
+    return fail(CHERT_ERR_INVALID_ARG, "workspace too small or unaligned");
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* ws = (uint8_t*)workspace_dev;
+  const int cn = P.cn, side = P.side, s2 = side * side;
+  const int K = (int)P.K;
+
+  // segment offsets (dx, dz) in [-cn, cn]^2 (the centre is never a segment:
+  // a stand-in offset keeps the lookups finite), lengths (eq 27), columns
+  std::vector<int32_t> tab((size_t)s2 * 3);
+  std::vector<double> L((size_t)s2);
+  for (int dz = -cn; dz <= cn; ++dz)
+    for (int dx = -cn; dx <= cn; ++dx) {
+      const int q = (dz + cn) * side + (dx + cn);
+      const int x = (dx == 0 && dz == 0) ? 1 : dx;
+      tab[q] = x;
+      tab[s2 + q] = dz;
+      const double ex = x * g->hx, ez = dz * g->hz;
+      L[q] = sqrt(ex * ex + ez * ez);
+      tab[2 * s2 + q] = 0;
+    }
+  if (!P.slow) {
+    std::vector<int32_t> bin((size_t)s2);
+    for (int q = 0; q < s2; ++q) bin[q] = star_bin_2d(tab[q], tab[s2 + q], g->hx, g->hz, d->n_dirs);
+    rc = star_columns(d, bin.data(), s2, tab.data() + 2 * s2);
+    if (rc) return rc;
+  }
+  double* dL = (double*)(ws + P.off_tab);  // lengths first: 8-byte aligned
+  int32_t* dtab = (int32_t*)(dL + s2);
+  int64_t* dsrc = (int64_t*)(ws + P.off_src);
+  hipError_t e = hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dL, L.data(), L.size() * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dsrc, src_nodes_host, (size_t)n_src * sizeof(int64_t),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // host buffers are locals
+  if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+
+  uint8_t* ctl = ws + P.off_ctl;
+  CellArgs a{};
+  a.ncx = g->ncx;
+  a.ncz = g->ncz;
+  a.cn = cn;
+  a.side = side;
+  a.NX = P.NX;
+  a.K = K;
+  a.n_src = n_src;
+  a.n_prob = P.n_prob;
+  a.n = P.n;
+  a.C = P.C;
+  a.cls = g->class_id_dev;
+  a.W = (const double*)(ws + P.off_W);
+  a.src = dsrc;
+  a.count = (int32_t*)ctl;
+  int32_t* err = (int32_t*)(ctl + 8);
+  a.alive = (int32_t*)(ctl + 12);
+  a.stats = (unsigned long long*)(ctl + 16);
+  double* wmin = (double*)(ctl + 48);
+  a.wmin = wmin;
+  a.minkey = (unsigned long long*)(ctl + 256);
+  a.lvl = (int32_t*)(ws + P.off_lvl);
+  a.active = (int32_t*)(ws + P.off_act);
+  a.key = (unsigned long long*)(ws + P.off_key);
+  a.list = (int32_t*)(ws + P.off_list);
+  a.hop = (int32_t*)(ws + P.off_hop);
+  a.bfs = (int32_t*)(ws + P.off_bfs);
+  a.bucket = o->bucket_width;
+  a.tree_mask = 0;
+  for (int fi = 0; fi < P.nfs; ++fi) {
+    const int f = P.fields[fi];
+    a.field_of[fi] = f;
+    a.tau[fi] = f ? tau_i_dev : tau_r_dev;
+    a.pred[fi] = f ? ((outs & CHERT_OUT_PRED_A) ? pred_a_dev : nullptr)
+                   : ((outs & CHERT_OUT_PRED_P) ? pred_p_dev : nullptr);
+    if (a.pred[fi]) a.tree_mask |= 1 << fi;
+  }
+  a.tstar = (outs & CHERT_OUT_TSTAR) ? tstar_dev : nullptr;
+
+  // class ids checked before any output is written
+  CHERT_LAUNCH("k_cell_zero", k_cell_zero, dim3(1), dim3(1), 0, s, err);
+  enqueue_class_check(g->class_id_dev, P.n, K, err, s);
+  {
+    int32_t herr = 0;
+    e = hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+    if (herr) return fail(CHERT_ERR_INVALID_ARG, "class id out of range");
+  }
+
+  // weights of both fields for every class pair and segment offset
+  chert_cache_layout lay;
+  chert_cache_layout_of(d, n_classes, &lay);
+  const uint8_t* cache = (const uint8_t*)cache_dev;
+  const int64_t ent = 3 * P.K * (int64_t)P.n_cols;
+  const int64_t mslice = (int64_t)mode * P.K * P.n_cols;
+  const double* fields = (const double*)(cache + lay.fields_offset);
+  const int32_t* Sm = (const int32_t*)(cache + lay.status_offset) + mslice;
+  int32_t* best = nullptr;
+  if (P.slow) {
+    best = (int32_t*)(ws + P.off_best);
+    enqueue_slow_lookup(best, K, P.n_cols, fields + CHERT_F_RX * ent + mslice,
+                        fields + CHERT_F_RZ * ent + mslice, Sm, s2, dtab, dtab + s2, g->hx,
+                        g->hz, s);
+  }
+  enqueue_pair_weights((double*)(ws + P.off_W), K, s2, fields + CHERT_F_V * ent + mslice,
+                       fields + CHERT_F_A * ent + mslice, Sm, P.n_cols, dL, dtab + 2 * s2, best,
+                       s);
+  enqueue_wmin_init(wmin, s);
+  if (a.bucket > 0.0) enqueue_wmin((const double*)(ws + P.off_W), P.K * P.K * s2, wmin, s);
+
+  const unsigned gfill = (unsigned)((P.n + 255) / 256 > 256 ? 256 : (P.n + 255) / 256);
+  CHERT_LAUNCH("k_cell_fill", k_cell_fill, dim3(gfill, (unsigned)P.n_prob), dim3(256), 0, s, a);
+  const unsigned gp = (unsigned)((P.n_prob + 255) / 256);
+  CHERT_LAUNCH("k_cell_seed", k_cell_seed, dim3(gp), dim3(256), 0, s, a);
+
+  // traveltime rounds, the host checking the round's list size every group
+  const int64_t items = (int64_t)P.n_prob * P.C;
+  const unsigned gsel = (unsigned)((items + 255) / 256 > 2048 ? 2048 : (items + 255) / 256);
+  const unsigned grelax = (unsigned)((items + kCellWaves - 1) / kCellWaves > 4096
+                                         ? 4096
+                                         : (items + kCellWaves - 1) / kCellWaves);
+  int rounds = -1;
+  for (int r = 0; r < P.max_rounds && rounds < 0;) {
+    const int group = r < 16 ? 16 : 32;
+    const int nb = r + group > P.max_rounds ? P.max_rounds - r : group;
+    for (int q = 0; q < nb; ++q) {
+      if (a.bucket > 0.0)
+        CHERT_LAUNCH("k_cell_minkey", k_cell_minkey, dim3(gsel), dim3(256), 0, s, a, r + q);
+      CHERT_LAUNCH("k_cell_select", k_cell_select, dim3(gsel), dim3(256), 0, s, a, r + q);
+      CHERT_LAUNCH("k_cell_relax", k_cell_relax, dim3(grelax), dim3(kCellThreads), 0, s, a,
+                   r + q);
+    }
+    r += nb;
+    int32_t cnt = 0;
+    e = hipMemcpyAsync(&cnt, a.count + ((r - 1) & 1), sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+    if (o->abort_flag_host && *o->abort_flag_host)
+      return fail(CHERT_ERR_ABORTED, "aborted by the caller");
+    if (cnt == 0) rounds = r;
+  }
+  if (rounds < 0) return fail(CHERT_ERR_NO_CONVERGENCE, "round cap reached");
+
+  // predecessors and t*: one level per launch, the host checking every group
+  int levels = 0;
+  if (a.tree_mask) {
+    unsigned gx = (unsigned)(2048 / P.n_prob);
+    if (gx < 1) gx = 1;
+    if (gx > 64) gx = 64;
+    bool done = false;
+    for (int Lv = 0; !done;) {
+      CHERT_LAUNCH("k_cell_zero", k_cell_zero, dim3(1), dim3(1), 0, s, a.alive);
+      for (int q = 0; q < 8; ++q, ++Lv) {
+        CHERT_LAUNCH("k_cell_level", k_cell_level, dim3(gx, (unsigned)P.n_prob),
+                     dim3(kCellThreads), 0, s, a, Lv);
+        CHERT_LAUNCH("k_cell_level_advance", k_cell_level_advance, dim3(gp), dim3(256), 0, s, a);
+      }
+      int32_t alive = 0;
+      e = hipMemcpyAsync(&alive, a.alive, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+      if (o->abort_flag_host && *o->abort_flag_host)
+        return fail(CHERT_ERR_ABORTED, "aborted by the caller");
+      if (alive == 0) {
+        done = true;
+        levels = Lv;
+      } else if (Lv > P.n + 8) {
+        return fail(CHERT_ERR_HIP, "BFS did not end");
+      }
+    }
+  }
+  if (o->stats_host) {
+    unsigned long long st[3] = {0, 0, 0};
+    e = hipMemcpyAsync(st, a.stats, sizeof(st), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+    chert_trace_stats* ts = o->stats_host;
+    memset(ts, 0, sizeof(*ts));
+    ts->rounds[0] = rounds;
+    ts->rounds[1] = levels;
+    ts->tile_visits[0] = (int64_t)st[0];
+    ts->edge_relaxations[0] = (int64_t)st[1];
+    ts->levels_sum[0] = (int64_t)st[2];
+  }
+  return CHERT_OK;
+}

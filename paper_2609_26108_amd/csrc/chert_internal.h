@@ -28,6 +28,10 @@ int fail(int code, const char* msg);
 int star_2d(int R, double hx, double hz, int n_dirs, int32_t* ox, int32_t* oz, double* L,
             int32_t* bin);
 
+// Bin of one offset (x, z) != 0 under the star's rule (nearest tabulated
+// direction, half-plane tie rounding); also for non-primitive offsets.
+int32_t star_bin_2d(int x, int z, double hx, double hz, int n_dirs);
+
 // Fibonacci ray directions f[3 N] (x, y, z) and the 3D forward star: offsets
 // with max norm <= R, gcd 1, ordered by (oy, oz, ox); lengths; bins = the
 // nearest Fibonacci direction (largest dot product, lowest index on ties).
@@ -92,6 +96,19 @@ int enqueue_weights_node_2d(double* W, int nx, int nz, int n_off, const int32_t*
                             const int32_t* oz_dev, const double* L_dev, const int32_t* col_dev,
                             int n_cols, const double* V, const double* A, const int32_t* st,
                             hipStream_t s);
+
+// Class-pair weights W[f][ki][kj][o] (eqs 28-30) over an offset list whose
+// lengths L and cache columns col live on the device; best (nullable): per
+// (class, offset) column of a slowness-sampled cache, read instead of col
+// (trace.hip).
+int enqueue_pair_weights(double* W, int K, int n_off, const double* V, const double* A,
+                         const int32_t* st, int n_cols, const double* L_dev,
+                         const int32_t* col_dev, const int32_t* best, hipStream_t s);
+// The closest stored ray direction of every class to every offset of a
+// list (slowness-sampled caches, trace.hip).
+int enqueue_slow_lookup(int32_t* best, int K, int n_cols, const double* RX, const double* RZ,
+                        const int32_t* st, int n_off, const int32_t* ox_dev,
+                        const int32_t* oz_dev, double hx, double hz, hipStream_t s);
 
 // Kernel timing for chert_prof_*: returns a slot (or -1 when profiling is
 // off) after recording a start event on the stream; prof_end records the stop.

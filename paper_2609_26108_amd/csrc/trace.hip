@@ -289,6 +289,26 @@ int enqueue_class_check(const int32_t* cls, int64_t n, int K, int32_t* err, hipS
   return CHERT_OK;
 }
 
+int enqueue_pair_weights(double* W, int K, int n_off, const double* V, const double* A,
+                         const int32_t* st, int n_cols, const double* L_dev,
+                         const int32_t* col_dev, const int32_t* best, hipStream_t s) {
+  const int64_t tw = 2LL * K * K * n_off;
+  const int64_t blocks = (tw + 255) / 256;
+  CHERT_LAUNCH("k_weights", k_weights, dim3((unsigned)(blocks > 65536 ? 65536 : blocks)),
+               dim3(256), 0, s, W, K, n_off, V, A, st, n_cols, L_dev, col_dev, best);
+  return CHERT_OK;
+}
+
+int enqueue_slow_lookup(int32_t* best, int K, int n_cols, const double* RX, const double* RZ,
+                        const int32_t* st, int n_off, const int32_t* ox_dev,
+                        const int32_t* oz_dev, double hx, double hz, hipStream_t s) {
+  const int64_t tl = (int64_t)K * n_off;
+  const int64_t blocks = (tl + 255) / 256;
+  CHERT_LAUNCH("k_slow_lookup", k_slow_lookup, dim3((unsigned)(blocks > 4096 ? 4096 : blocks)),
+               dim3(256), 0, s, best, K, n_cols, RX, RZ, st, n_off, ox_dev, oz_dev, hx, hz);
+  return CHERT_OK;
+}
+
 int enqueue_weights_node_2d(double* W, int nx, int nz, int n_off, const int32_t* ox_dev,
                             const int32_t* oz_dev, const double* L_dev, const int32_t* col_dev,
                             int n_cols, const double* V, const double* A, const int32_t* st,

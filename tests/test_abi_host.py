@@ -353,7 +353,8 @@ def test_abi_struct_layouts_match_header(tmp_path):
     structs = {"chert_class": C.ChertClass, "chert_cache_desc": C.CacheDesc,
                "chert_cache_layout": C.CacheLayout, "chert_cache_stats": C.CacheStats,
                "chert_grid": C.Grid, "chert_trace_job": C.TraceJob,
-               "chert_trace_stats": C.TraceStats, "chert_trace_opts": C.TraceOpts}
+               "chert_trace_stats": C.TraceStats, "chert_trace_opts": C.TraceOpts,
+               "chert_cell_grid": C.CellGrid}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "chert.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -371,3 +372,26 @@ def test_abi_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_cell_network_validation():
+    """Host checks of the cell-network trace (no device call): workspace
+    bytes for valid networks, 0 for bad ones; the workspace grows with the
+    sources."""
+    d = C.cache_desc(n_dirs=360, modes=(0, 1))
+    o = C.trace_opts(C.OUT_ALL)
+    fake = 0x1000  # never dereferenced by the size query
+
+    def g(ncx=10, ncz=6, cn=5, hx=10.0, hz=10.0, cls=fake):
+        return C.CellGrid(ncx, ncz, cn, 0, hx, hz, cls)
+
+    b1 = C.chert_trace_cells_workspace_bytes(d, 3, g(), 1, o)
+    b4 = C.chert_trace_cells_workspace_bytes(d, 3, g(), 4, o)
+    assert 0 < b1 < b4
+    assert C.chert_trace_cells_workspace_bytes(d, 3, g(cn=16), 1, o) > 0
+    for bad in (g(cn=0), g(cn=17), g(ncx=0), g(hx=0.0), g(hz=float("nan")), g(cls=None)):
+        assert C.chert_trace_cells_workspace_bytes(d, 3, bad, 1, o) == 0
+    assert C.chert_trace_cells_workspace_bytes(C.cache_desc(dim=3, n_dirs=500), 3, g(), 1, o) == 0
+    assert C.chert_trace_cells_workspace_bytes(d, 3, g(), 1, C.trace_opts(C.OUT_TSTAR)) == 0
+    assert C.chert_trace_cells_workspace_bytes(
+        C.cache_desc(n_dirs=72, modes=(2,), sampling=C.SAMPLE_SLOWNESS), 3, g(), 1, o) > 0
