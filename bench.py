@@ -23,7 +23,8 @@ Other workloads print their own line: `layered` (the 5-layer model, class
 caches), `complex2d` (per-node caches of the 1701x351 model, k-means
 ablation), `3d` (the 201x201x101 layered model), `ablation` (angular step
 and star radius), `local` (the OEV-versus-MEV sweep on rock layer 1 with
-slowness- and ray-sampled caches).
+slowness- and ray-sampled caches), `cells` (the cell network on the layered
+model).
 """
 from __future__ import annotations
 
@@ -124,7 +125,7 @@ def parse():
                    help="complex2d, shots: trace with the default (or given) launch options")
     p.add_argument("--bucket", type=float, default=0.0,
                    help="node-frontier near/far bucket width (units of the smallest weight)")
-    p.add_argument("--workload", choices=("shots", "layered", "complex2d", "3d", "ablation", "local"),
+    p.add_argument("--workload", choices=("shots", "layered", "complex2d", "3d", "ablation", "local", "cells"),
                    default="shots",
                    help="shots: 128 shots over 4 uneven per-node grids, surrogate-started "
                         "caches + one batched trace per step (default, the headline line); "
@@ -188,6 +189,9 @@ def main():
         return
     if args.workload == "local":
         run_local(args)
+        return
+    if args.workload == "cells":
+        run_cells(args)
         return
     m = W.config2()
     K = len(m.layers)
@@ -1275,6 +1279,159 @@ def run_local(args):
     res["value"] = timing["MEV"]["solves_per_s"]
     res["unit"] = "Hamiltonian solves/s (slowness-sampled MEV, rock layer 1, 3 modes)"
     res["higher_is_better"] = True
+    print(json.dumps(res))
+
+
+CELL_BUCKETS = (0.0, 4.0, 16.0, 64.0)
+
+
+def cell_pairs(ncx, ncz, cn):
+    """Directed segments of the cell network: ordered pairs of distinct
+    boundary nodes per cell (a pair along an edge shared by two cells is
+    counted once per cell)."""
+    nb = 4 * cn
+    return ncx * ncz * nb * (nb - 1)
+
+
+def run_cells(args):
+    """The paper's cell network (nodes on cell edges, every boundary pair of
+    a cell a segment; eqs 23-24, 27-32) on the layered model: cells of 5x5
+    lattice intervals over the 401x201 lattice at 5 m (80x40 cells), class
+    caches at 1 degree, qP/qSV/qSH from the surface source.  Timed per mode
+    with every woken cell per round and with block-ordered rounds of several
+    widths; traveltimes compared with the radius-5 forward star on the same
+    lattice (the node density study's comparison at matched angular
+    coverage)."""
+    import torch
+    import paper_2609_26108_amd as C
+    import workloads as W
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    m = W.config2()
+    cn = 5
+    ncx, ncz = (m.nx - 1) // cn, (m.nz - 1) // cn
+    K = len(m.layers)
+    cls = torch.from_numpy(np.stack([C.chert_class_from_thomsen(*L.thomsen_args()).as_array()
+                                     for L in m.layers])).to(dev)
+    desc = C.cache_desc(n_dirs=360, modes=m.modes)
+    lay = C.chert_cache_layout_of(desc, K)
+    cache = torch.zeros(lay.total_bytes, dtype=torch.uint8, device=dev)
+    ws = torch.empty(max(C.chert_build_cache_workspace_bytes(desc, K), 1), dtype=torch.uint8,
+                     device=dev)
+    C.chert_build_cache(desc, cls, K, cache, ws, stream=stream)
+    cid = torch.from_numpy(m.class_id.reshape(-1).astype(np.int32)).to(dev)
+    cg = C.make_cell_grid(ncx, ncz, cn, m.hx, m.hz, cid)
+    n = m.n_nodes
+    ix = np.arange(m.nx)[None, :]
+    iz = np.arange(m.nz)[:, None]
+    node_mask = torch.from_numpy(((ix % cn == 0) | (iz % cn == 0)).reshape(-1)).to(dev)
+    pairs = cell_pairs(ncx, ncz, cn)
+    res = {"metric": METRIC, "workload": "cells", "n_gpus": 1, "dtype": "f64",
+           "data": "synthetic (seeded workloads.config2)",
+           "config": {"workload": f"cell network {ncx}x{ncz} cells of {cn}x{cn} intervals on "
+                                  "the 5-layer 401x201 lattice @5 m, 1-degree class caches, "
+                                  "qP/qSV/qSH, one surface source",
+                      "network_nodes": int(node_mask.sum().item()), "segments": pairs}}
+    outs = C.OUT_ALL
+    per = {}
+    taus = {}
+    for bw in CELL_BUCKETS:
+        row = {}
+        for mode in m.modes:
+            st = C.TraceStats()
+            o = C.trace_opts(outs, bucket_width=bw, stats=st)
+            t = {k: torch.empty((1, n), dtype=dt, device=dev) for k, dt in
+                 (("tr", torch.float64), ("ti", torch.float64), ("ts", torch.float64),
+                  ("pp", torch.int32), ("pa", torch.int32))}
+            tws = torch.empty(C.chert_trace_cells_workspace_bytes(desc, K, cg, 1, o),
+                              dtype=torch.uint8, device=dev)
+            C.chert_trace_cells(desc, cache, K, cg, mode, m.sources, o, t["tr"], t["ti"],
+                                t["ts"], t["pp"], t["pa"], tws, stream=stream)
+            times = []
+            for _ in range(max(args.steps, 1)):
+                ev = _events(torch, stream)
+                C.chert_trace_cells(desc, cache, K, cg, mode, m.sources, o, t["tr"], t["ti"],
+                                    t["ts"], t["pp"], t["pa"], tws, stream=stream)
+                times.append(_elapsed(torch, ev, stream))
+            ts = float(np.median(times))
+            # the traveltime phase alone (no predecessors)
+            st2 = C.TraceStats()
+            o2 = C.trace_opts(C.OUT_TAU_R | C.OUT_TAU_I, bucket_width=bw, stats=st2)
+            C.chert_prof_enable(True)
+            C.chert_trace_cells(desc, cache, K, cg, mode, m.sources, o2, t["tr"], t["ti"],
+                                None, None, None, tws, stream=stream)
+            torch.cuda.synchronize()
+            prof = C.chert_prof_read()
+            C.chert_prof_enable(False)
+            relax_s = prof.get("k_cell_relax", (0, 0.0))[1] * 1e-3
+            row[str(mode)] = {"s": ts, "rounds": st.rounds[0], "bfs_levels": st.rounds[1],
+                              "cell_visits": st.tile_visits[0],
+                              "pair_relaxations": st.edge_relaxations[0],
+                              "relax_kernel_s": relax_s,
+                              "relax_kernel_pairs": st2.edge_relaxations[0],
+                              "pair_relaxations_per_s": st2.edge_relaxations[0] / max(relax_s, 1e-12)}
+            if bw == 0.0:
+                taus[mode] = t["tr"][0].clone()
+        per[f"bucket_{bw:g}"] = row
+    res["modes"] = per
+    # forward star of radius 5 on the same lattice, at the network's nodes
+    grid = C.make_grid(m.nx, m.nz, m.hx, m.hz, 5, cid)
+    o = C.trace_opts(C.OUT_TAU_R)
+    cmp = {}
+    for mode in m.modes:
+        tr = torch.empty((1, n), dtype=torch.float64, device=dev)
+        tws = torch.empty(C.chert_trace_workspace_bytes(desc, K, grid, 1, o), dtype=torch.uint8,
+                          device=dev)
+        C.chert_trace_field(desc, cache, K, grid, mode, m.sources, o, tr, None, None, None, None,
+                            tws, stream=stream)
+        torch.cuda.synchronize()
+        cmp[str(mode)] = _misfit(taus[mode][node_mask], tr[0][node_mask])
+    res["cells_vs_star_R5_tauR"] = cmp
+    # a batch of surface sources per call: the rounds of all problems share
+    # the launches
+    n_batch = 16
+    bsrc = [int(x) for x in np.linspace(0, ncx, n_batch).astype(int) * cn]
+    bres = {}
+    for bw in (0.0, 16.0):
+        tot = 0.0
+        for mode in m.modes:
+            o = C.trace_opts(outs, bucket_width=bw)
+            t = {k: torch.empty((n_batch, n), dtype=dt, device=dev) for k, dt in
+                 (("tr", torch.float64), ("ti", torch.float64), ("ts", torch.float64),
+                  ("pp", torch.int32), ("pa", torch.int32))}
+            tws = torch.empty(C.chert_trace_cells_workspace_bytes(desc, K, cg, n_batch, o),
+                              dtype=torch.uint8, device=dev)
+            C.chert_trace_cells(desc, cache, K, cg, mode, bsrc, o, t["tr"], t["ti"], t["ts"],
+                                t["pp"], t["pa"], tws, stream=stream)
+            ev = _events(torch, stream)
+            C.chert_trace_cells(desc, cache, K, cg, mode, bsrc, o, t["tr"], t["ti"], t["ts"],
+                                t["pp"], t["pa"], tws, stream=stream)
+            tot += _elapsed(torch, ev, stream)
+        bres[f"bucket_{bw:g}"] = {"s_all_modes": tot,
+                                  "fields_per_s": len(m.modes) * n_batch / tot}
+    res["batch_16_sources"] = bres
+    best = min(per.values(), key=lambda r: sum(v["s"] for v in r.values()))
+    res["value"] = max(v["fields_per_s"] for v in bres.values())
+    res["unit"] = ("fields/s (tau_R, tau_I, predecessors and t* per source and mode, "
+                   "16 sources per call, cell network)")
+    res["higher_is_better"] = True
+    # ALU roofline of the pair relaxation: one add and one compare per pair
+    dom = max(best.values(), key=lambda v: v["relax_kernel_s"])
+    ach = 2.0 * dom["relax_kernel_pairs"] / max(dom["relax_kernel_s"], 1e-12) / 1e12
+    res["roofline"] = {"bound": "alu", "achieved": ach, "peak": FP64_VALU_PEAK_TOPS,
+                       "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK_TOPS, "traffic": None,
+                       "kernel": "k_cell_relax"}
+    if not args.no_cpu:
+        import oracle as O
+        cls_np = np.stack([O.class_from_thomsen(*L.thomsen_args()) for L in m.layers])
+        f, st = O.build_cache_2d(cls_np, n_dirs=360, mode_mask=0b001)
+        t0 = time.perf_counter()
+        O.trace_cells_2d(ncx, ncz, cn, m.hx, m.hz, m.class_id, f[:, 0], st[0], m.sources[0])
+        el = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": 1.0 / el, "unit": "fields/s (all five outputs, qP)",
+                               "cores": 1, "kind": "oracle",
+                               "sample": "one qP field of the same network (node Dijkstra, "
+                                         "predecessors, t*)"}
     print(json.dumps(res))
 
 

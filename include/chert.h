@@ -516,7 +516,7 @@ size_t chert_trace_cells_workspace_bytes(const chert_cache_desc *d, int64_t n_cl
  * [n_src][NX NZ] under the same output-mask rules as chert_trace_field;
  * lattice points inside cells get +inf (tau, t*) and -1 (pred).  Options
  * read: outputs, max_rounds, bucket_width, stats_host (rounds[0] =
- * traveltime rounds, rounds[1] = BFS levels launched, tile_visits[0] = cell
+ * traveltime rounds, rounds[1] = BFS levels of the deepest tree, tile_visits[0] = cell
  * visits, edge_relaxations[0] = pair relaxations, levels_sum[0] = passes
  * over the pairs of the visited cells), abort_flag_host; the tile fields and
  * launch are ignored.  INVALID_ARG on a source inside a cell, a class id out

@@ -5,8 +5,9 @@
 //
 // Traveltimes: one wave per (problem, cell) visit, one lane per boundary node
 // (4 cn <= 64).  The wave loads its cell's traveltimes and classes once,
-// then relaxes every ordered pair (eq 31) from lane broadcasts until a pass
-// changes nothing (Jacobi passes inside the cell), and lowers the improved
+// stages the weights of the cell's ordered pairs in LDS, then relaxes every
+// ordered pair (eq 31) from lane broadcasts until a pass changes nothing
+// (Jacobi passes inside the cell), and lowers the improved
 // nodes in HBM with a 64-bit atomicMin on the traveltime bits (traveltimes
 // are >= 0, so their bit patterns order like the values).  A cell is woken
 // with key = the smallest improved traveltime among its nodes (the block
@@ -17,11 +18,12 @@
 // traveltimes whatever the schedule.
 //
 // Predecessors and t*: level-synchronous BFS over tight segments
-// (tau_i + w_ij == tau_j) from the source, one wave per node of the current
-// level, lanes over the boundary nodes of the node's cells: pred_j = the
-// tight neighbour one level up with the smallest node index (the smallest
-// (hop, index) among all tight neighbours), t*_j = t*_pred + the attenuation
-// weight of that segment, each parent's value final one level earlier.
+// (tau_i + w_ij == tau_j) from the source, one launch per level, threads
+// over (node, cell, boundary slot) triples: pred_j = the tight neighbour one
+// level up with the smallest node
+// index (the smallest (hop, index) among all tight neighbours), t*_j =
+// t*_pred + the attenuation weight of that segment, each parent's value
+// final one level earlier.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -49,6 +51,13 @@ __device__ __forceinline__ double bcast_d(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// order one wave's LDS writes before its later LDS reads (other lanes')
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // boundary slot s of a cell of side cn -> local lattice point (lx, lz):
@@ -103,7 +112,7 @@ struct CellArgs {
   const int64_t* src;  // [n_src]
   int32_t* active;     // [P][C]
   unsigned long long* key;     // [P][C]
-  unsigned long long* minkey;  // [2][P] (round parity)
+  unsigned long long* minkey;  // [3][P]: round r reads slot r % 3
   int32_t* list;               // [P C] selected (problem, cell) items
   int32_t* count;              // [2] (round parity)
   unsigned long long* stats;   // visits, pair relaxations, passes
@@ -112,8 +121,10 @@ struct CellArgs {
   // level phase
   int32_t* hop;        // [P][n]
   int32_t* bfs;        // [P][n] BFS order
-  int32_t* lvl;        // [3][P]: start, end, tail
-  int32_t* alive;      // nodes added since the host last looked
+  int32_t* bid;        // [P][n] predecessor bids (atomicMin)
+  int32_t* bnd;        // [3][P] end of level L in slot L % 3
+  int32_t* cnt;        // [3][P] nodes appended during level L in slot L % 3
+  int32_t* alive;      // most BFS levels over the problems
   int32_t* pred[2];    // per field slot, rows [n_src][n] (nullable)
   double* tstar;       // rows [n_src][n] for the propagation slot (nullable)
   int tree_mask;       // bit fi: problems of field slot fi need the tree
@@ -132,10 +143,12 @@ __global__ void k_cell_fill(CellArgs a) {
   int32_t* pr = a.pred[fi] ? a.pred[fi] + (int64_t)s * a.n : nullptr;
   double* ts = (a.tstar && a.field_of[fi] == 0) ? a.tstar + (int64_t)s * a.n : nullptr;
   int32_t* hp = a.hop + (int64_t)p * a.n;
+  int32_t* bd = a.bid + (int64_t)p * a.n;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
        i += (int64_t)gridDim.x * blockDim.x) {
     t[i] = INFINITY;
     hp[i] = -1;
+    bd[i] = 0x7fffffff;
     if (pr) pr[i] = -1;
     if (ts) ts[i] = INFINITY;
   }
@@ -147,8 +160,9 @@ __global__ void k_cell_fill(CellArgs a) {
     ky[c] = kInfBits;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    a.minkey[p] = kInfBits;
+    a.minkey[p] = 0ull;  // round 0 takes the source's cells (key 0)
     a.minkey[a.n_prob + p] = kInfBits;
+    a.minkey[2 * a.n_prob + p] = kInfBits;
   }
   if (p == 0 && blockIdx.x == 0 && threadIdx.x < 8) {
     if (threadIdx.x < 2) a.count[threadIdx.x] = 0;
@@ -157,7 +171,7 @@ __global__ void k_cell_fill(CellArgs a) {
   }
 }
 
-// the source: tau = 0, its cells woken with key 0; the level phase seeded
+// the source: tau = 0, its cells woken with key 0
 __global__ void k_cell_seed(CellArgs a) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= a.n_prob) return;
@@ -170,37 +184,26 @@ __global__ void k_cell_seed(CellArgs a) {
     a.active[(int64_t)p * a.C + cs[q]] = 1;
     a.key[(int64_t)p * a.C + cs[q]] = 0ull;
   }
-  int32_t* lv = a.lvl;
+  // level 0 of the BFS: the source alone (end of "level -1" = 0, one node)
   if ((a.tree_mask >> fi) & 1) {
     a.hop[(int64_t)p * a.n + src] = 0;
     a.bfs[(int64_t)p * a.n] = (int32_t)src;
-    lv[p] = 0;                   // start
-    lv[a.n_prob + p] = 1;        // end
-    lv[2 * a.n_prob + p] = 1;    // tail
     if (a.tstar && a.field_of[fi] == 0) a.tstar[(int64_t)s * a.n + src] = 0.0;
-  } else {
-    lv[p] = lv[a.n_prob + p] = lv[2 * a.n_prob + p] = 0;
   }
+  a.bnd[2 * a.n_prob + p] = 0;
+  a.cnt[2 * a.n_prob + p] = ((a.tree_mask >> fi) & 1) ? 1 : 0;
+  a.cnt[p] = 0;
+  a.cnt[a.n_prob + p] = 0;
 }
 
-// round r, step 1 (ordered rounds only): each problem's smallest key
-__global__ void k_cell_minkey(CellArgs a, int r) {
-  const int64_t total = (int64_t)a.n_prob * a.C;
-  unsigned long long* mk = a.minkey + (int64_t)(r & 1) * a.n_prob;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    if (!a.active[t]) continue;
-    const int p = (int)(t / a.C);
-    const unsigned long long k = a.key[t];
-    if (k < mk[p]) atomicMin(&mk[p], k);
-  }
-}
-
-// round r, step 2: take the woken cells (within the width of the smallest
-// key when ordered) into this round's list; reset the other parity's slots
+// round r, step 1: take the woken cells (when ordered: those whose key is
+// within the width of the problem's smallest key, slot r % 3, which the
+// previous round's select and relax filled) into this round's list; the
+// cells left waiting bid their keys for the next round's minimum
 __global__ void k_cell_select(CellArgs a, int r) {
   const int64_t total = (int64_t)a.n_prob * a.C;
-  const unsigned long long* mk = a.minkey + (int64_t)(r & 1) * a.n_prob;
+  const unsigned long long* mk = a.minkey + (int64_t)(r % 3) * a.n_prob;
+  unsigned long long* mk_next = a.minkey + (int64_t)((r + 1) % 3) * a.n_prob;
   int32_t* cnt = a.count + (r & 1);
   const int lane = __lane_id();
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total;
@@ -212,8 +215,10 @@ __global__ void k_cell_select(CellArgs a, int r) {
       if (a.bucket > 0.0) {
         const int p = (int)(t / a.C);
         const int f = a.field_of[p / a.n_src];
+        const unsigned long long k = a.key[t];
         const double lim = __longlong_as_double((long long)mk[p]) + a.bucket * a.wmin[f];
-        take = __longlong_as_double((long long)a.key[t]) <= lim;
+        take = __longlong_as_double((long long)k) <= lim;
+        if (!take) atomicMin(&mk_next[p], k);
       }
     }
     const unsigned long long m = __ballot(take);
@@ -230,23 +235,30 @@ __global__ void k_cell_select(CellArgs a, int r) {
       }
     }
   }
-  // the next round's counter and minima start afresh (this round's relax
-  // reads only this parity; the previous round's relax has finished)
+  // the next round's counter and the round after next's minima start afresh
+  // (slot (r + 2) % 3 was last read by the previous round's select)
   if (blockIdx.x == 0) {
     if (threadIdx.x == 0) a.count[(r + 1) & 1] = 0;
-    unsigned long long* nm = a.minkey + (int64_t)((r + 1) & 1) * a.n_prob;
+    unsigned long long* nm = a.minkey + (int64_t)((r + 2) % 3) * a.n_prob;
     for (int p = threadIdx.x; p < a.n_prob; p += blockDim.x) nm[p] = kInfBits;
   }
 }
 
-// round r, step 3: relax the listed cells
+// round r, step 3: relax the listed cells.  Each visit first stages the
+// weights of its ns x ns ordered pairs in LDS (one batch of independent
+// loads per lane), then runs the passes from LDS and lane broadcasts.
 __global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) {
+  extern __shared__ double s_w[];  // [waves][ns][ns]
+  __shared__ unsigned long long s_wake[kCellWaves][8];  // per neighbour cell
   const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * kCellWaves + (threadIdx.x >> 6);
-  const int nw = gridDim.x * kCellWaves;
+  const int wib = threadIdx.x >> 6;
+  const int wpb = blockDim.x >> 6;
+  const int wave = blockIdx.x * wpb + wib;
+  const int nw = gridDim.x * wpb;
   const int count = a.count[r & 1];
   const int cn = a.cn, ns = 4 * cn, side = a.side, K = a.K;
   const int64_t s2 = (int64_t)side * side;
+  double* wl = s_w + (size_t)wib * ns * ns;
   int lx = 0, lz = 0;
   if (lane < ns) slot_xy(lane, cn, lx, lz);
   unsigned long long visits = 0, pairs = 0, passes_all = 0;
@@ -265,44 +277,81 @@ __global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) 
       k = a.cls[node];
       t = tau[node];
     }
+    // stage w(a -> lane) for every slot a (the diagonal is never read),
+    // eight loads in flight per lane; slot a's class and position come from
+    // lane a
+    {
+      const double* Wk = W + (int64_t)k * s2;  // column class = this lane's
+      for (int sa0 = 0; sa0 < ns; sa0 += 8) {
+        double w8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int sa = sa0 + u < ns ? sa0 + u : ns - 1;
+          const int ka = __builtin_amdgcn_readlane(k, sa);
+          const int ax = __builtin_amdgcn_readlane(lx, sa);
+          const int az = __builtin_amdgcn_readlane(lz, sa);
+          const int off = (lz - az + cn) * side + (lx - ax + cn);
+          w8[u] = lane < ns ? Wk[(int64_t)ka * K * s2 + off] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (lane < ns && sa0 + u < ns) wl[(sa0 + u) * ns + lane] = w8[u];
+      }
+    }
+    wave_sync_lds();
     const double t0 = t;
     int passes = 0;
     for (;;) {
       double best = t;
-      for (int s = 0; s < ns; ++s) {
-        const double ta = bcast_d(t, s);
-        if (!(ta < INFINITY)) continue;  // uniform: no path into slot s yet
-        const int ka = __builtin_amdgcn_readlane(k, s);
-        int ax, az;
-        slot_xy(s, cn, ax, az);
-        if (lane < ns && lane != s) {
-          const int off = (lz - az + cn) * side + (lx - ax + cn);
-          const double cand = ta + W[((int64_t)ka * K + k) * s2 + off];
-          if (cand < best) best = cand;
-        }
+#pragma unroll 4
+      for (int sa = 0; sa < ns; ++sa) {
+        const double ta = bcast_d(t, sa);
+        // +inf + w stays +inf, and slot sa's own lane reads the unused
+        // diagonal, so every lane can add without a branch
+        const double cand = ta + wl[sa * ns + (lane < ns ? lane : 0)];
+        if (lane < ns && lane != sa && cand < best) best = cand;
       }
       ++passes;
       const bool ch = best < t;
       t = best;
       if (!__ballot(ch)) break;
     }
+    wave_sync_lds();  // LDS reused by the wave's next item
     ++visits;
     pairs += (unsigned long long)passes * ns * (ns - 1);
     passes_all += passes;
+    // lower the improved nodes; each of the 8 neighbouring cells is woken
+    // once, with the smallest new traveltime among the nodes it shares
+    if (lane < 8) s_wake[wib][lane] = kInfBits;
+    wave_sync_lds();
     if (lane < ns && t < t0) {
       const unsigned long long nb = dbits(t);
       const unsigned long long old = atomicMin((unsigned long long*)&tau[node], nb);
-      if (nb < old) {  // wake the node's other cells
-        int cs[4];
-        const int nc = cells_of(gx, gz, cn, a.ncx, a.ncz, cs);
-        for (int q = 0; q < nc; ++q) {
-          if (cs[q] == c) continue;
-          const int64_t e = (int64_t)p * a.C + cs[q];
-          atomicMin(&a.key[e], nb);
-          a.active[e] = 1;
-        }
+      if (nb < old) {
+        const int ex = lx == 0 ? -1 : (lx == cn ? 1 : 0);
+        const int ez = lz == 0 ? -1 : (lz == cn ? 1 : 0);
+        // neighbour d = (dx + 1) + 3 (dz + 1), skipping the cell itself
+        for (int dz = -1; dz <= 1; ++dz)
+          for (int dx = -1; dx <= 1; ++dx) {
+            if ((dx == 0 && dz == 0) || (dx != 0 && dx != ex) || (dz != 0 && dz != ez)) continue;
+            const int d = (dx + 1) + 3 * (dz + 1);
+            atomicMin(&s_wake[wib][d < 4 ? d : d - 1], nb);
+          }
       }
     }
+    wave_sync_lds();
+    if (lane < 8) {
+      const unsigned long long v = s_wake[wib][lane];
+      const int d = lane < 4 ? lane : lane + 1;
+      const int nx = cx + d % 3 - 1, nz = cz + d / 3 - 1;
+      if (v != kInfBits && nx >= 0 && nx < a.ncx && nz >= 0 && nz < a.ncz) {
+        const int64_t e = (int64_t)p * a.C + nx + (int64_t)a.ncx * nz;
+        atomicMin(&a.key[e], v);
+        a.active[e] = 1;
+        if (a.bucket > 0.0) atomicMin(&a.minkey[(int64_t)((r + 1) % 3) * a.n_prob + p], v);
+      }
+    }
+    wave_sync_lds();
   }
   if (lane == 0 && visits) {
     atomicAdd(&a.stats[0], visits);
@@ -311,84 +360,91 @@ __global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) 
   }
 }
 
-// level L of the BFS over tight segments: grid (x, problem); one wave per
-// node j of the level.  Lanes walk the boundary nodes v of j's cells:
-// pred_j = the smallest v one level up with tau_v + w(v->j) == tau_j;
-// every v not yet reached with tau_j + w(j->v) == tau_v joins level L+1
-// (one winner per node through a compare-and-swap on its hop).
-__global__ void __launch_bounds__(kCellThreads) k_cell_level(CellArgs a, int L) {
+// Predecessors and t*, level L of the BFS over tight segments, one launch
+// per level, grid (x, problem).  Step 1 (level L): every thread takes
+// (node j of the level, one of j's cells, one boundary slot v of that cell)
+// triples: a tight v one level up (tau_v + w(v->j) == tau_j) bids for pred_j
+// with an atomicMin on its index; a v not yet reached with
+// tau_j + w(j->v) == tau_v joins level L + 1 (one winner per node through a
+// compare-and-swap on its hop).  Step 2 (level L - 1, whose bids were final
+// when the previous launch ended): pred_j and t*_j = t*_pred + the
+// attenuation weight of that segment (the parent's value final one level
+// earlier).  Level bounds rotate through three slots per problem.
+__global__ void __launch_bounds__(256) k_cell_level(CellArgs a, int L) {
   const int p = blockIdx.y;
   const int fi = p / a.n_src, s = p - fi * a.n_src;
   if (!((a.tree_mask >> fi) & 1)) return;
-  const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * kCellWaves + (threadIdx.x >> 6);
-  const int nw = gridDim.x * kCellWaves;
-  const int start = a.lvl[p], end = a.lvl[a.n_prob + p];
+  const int P = a.n_prob;
+  const int start = a.bnd[((L + 2) % 3) * P + p];
+  const int end = start + a.cnt[((L + 2) % 3) * P + p];
+  const int pstart = L >= 2 ? a.bnd[((L + 1) % 3) * P + p] : start;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.bnd[(L % 3) * P + p] = end;
+    a.cnt[((L + 1) % 3) * P + p] = 0;
+  }
+  int32_t* cnt = a.cnt + (L % 3) * P + p;
   const int cn = a.cn, ns = 4 * cn, side = a.side, K = a.K;
+  const int per = 4 * ns;  // (cell, slot) triples per node
   const int64_t s2 = (int64_t)side * side;
   const int f = a.field_of[fi];
   const double* W = a.W + (int64_t)f * K * K * s2;
+  const double* WI = a.W + (int64_t)K * K * s2;
   const double* tau = a.tau[fi] + (int64_t)s * a.n;
   int32_t* hop = a.hop + (int64_t)p * a.n;
   int32_t* bfs = a.bfs + (int64_t)p * a.n;
-  int32_t* tail = a.lvl + 2 * a.n_prob + p;
-  int lx = 0, lz = 0;
-  if (lane < ns) slot_xy(lane, cn, lx, lz);
+  int32_t* bid = a.bid + (int64_t)p * a.n;
+  int32_t* pred = a.pred[fi] ? a.pred[fi] + (int64_t)s * a.n : nullptr;
+  double* ts = (a.tstar && f == 0) ? a.tstar + (int64_t)s * a.n : nullptr;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
   int added = 0;
-  for (int idx = start + wave; idx < end; idx += nw) {
-    const int64_t j = bfs[idx];
+  const int64_t work = (int64_t)(end - start) * per;
+  for (int64_t t = tid; t < work; t += nthr) {
+    const int64_t j = bfs[start + (int)(t / per)];
+    const int q = (int)((t / ns) & 3), sl = (int)(t % ns);
     const int jx = (int)(j % a.NX), jz = (int)(j / a.NX);
-    const double tj = tau[j];
-    const int kj = a.cls[j];
     int cs[4];
     const int nc = cells_of(jx, jz, cn, a.ncx, a.ncz, cs);
-    int best = 0x7fffffff;
-    for (int q = 0; q < nc; ++q) {
-      const int vx = (cs[q] % a.ncx) * cn + lx, vz = (cs[q] / a.ncx) * cn + lz;
-      const int64_t v = (int64_t)vx + (int64_t)a.NX * vz;
-      if (lane >= ns || v == j) continue;
-      const int kv = a.cls[v];
-      const double tv = tau[v];
-      const int hv = hop[v];
-      if (L > 0 && hv == L - 1) {  // v -> j tight?
-        const int off = (jz - vz + cn) * side + (jx - vx + cn);
-        if (tv + W[((int64_t)kv * K + kj) * s2 + off] == tj && (int)v < best) best = (int)v;
-      }
-      if (hv == -1 && tv < INFINITY) {  // j -> v tight?
-        const int off = (vz - jz + cn) * side + (vx - jx + cn);
-        if (tj + W[((int64_t)kj * K + kv) * s2 + off] == tv &&
-            atomicCAS(&hop[v], -1, L + 1) == -1) {
-          bfs[atomicAdd(tail, 1)] = (int32_t)v;
-          ++added;
-        }
+    if (q >= nc) continue;
+    int lx, lz;
+    slot_xy(sl, cn, lx, lz);
+    const int vx = (cs[q] % a.ncx) * cn + lx, vz = (cs[q] / a.ncx) * cn + lz;
+    const int64_t v = (int64_t)vx + (int64_t)a.NX * vz;
+    if (v == j) continue;
+    const int kj = a.cls[j], kv = a.cls[v];
+    const double tj = tau[j], tv = tau[v];
+    const int hv = hop[v];
+    if (L > 0 && hv == L - 1) {  // v -> j tight?
+      const int off = (jz - vz + cn) * side + (jx - vx + cn);
+      if (tv + W[((int64_t)kv * K + kj) * s2 + off] == tj) atomicMin(&bid[j], (int)v);
+    }
+    if (hv == -1 && tv < INFINITY) {  // j -> v tight?
+      const int off = (vz - jz + cn) * side + (vx - jx + cn);
+      if (tj + W[((int64_t)kj * K + kv) * s2 + off] == tv && atomicCAS(&hop[v], -1, L + 1) == -1) {
+        bfs[end + atomicAdd(cnt, 1)] = (int32_t)v;
+        ++added;
       }
     }
-    if (L > 0) {
-      for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o));
-      // a node of level L always has a tight neighbour one level up (the
-      // one that reached it); the check only keeps the reads in bounds
-      if (lane == 0 && best != 0x7fffffff) {
-        if (a.pred[fi]) a.pred[fi][(int64_t)s * a.n + j] = best;
-        if (a.tstar && f == 0) {
-          const int64_t i = best;
-          const int ix = (int)(i % a.NX), iz = (int)(i / a.NX);
-          const int off = (jz - iz + cn) * side + (jx - ix + cn);
-          const double wI = a.W[(int64_t)K * K * s2 + ((int64_t)a.cls[i] * K + kj) * s2 + off];
-          a.tstar[(int64_t)s * a.n + j] = a.tstar[(int64_t)s * a.n + i] + wI;
-        }
+  }
+  if (L >= 2) {
+    for (int64_t idx = pstart + tid; idx < start; idx += nthr) {
+      const int64_t j = bfs[idx];
+      const int b = bid[j];
+      // a node one level below the source always has a tight neighbour one
+      // level up (the one that reached it); the check only keeps the reads
+      // in bounds
+      if (b == 0x7fffffff) continue;
+      if (pred) pred[j] = b;
+      if (ts) {
+        const int jx = (int)(j % a.NX), jz = (int)(j / a.NX);
+        const int ix = b % a.NX, iz = b / a.NX;
+        const int off = (jz - iz + cn) * side + (jx - ix + cn);
+        ts[j] = ts[b] + WI[((int64_t)a.cls[b] * K + a.cls[j]) * s2 + off];
       }
     }
   }
   for (int o = 32; o > 0; o >>= 1) added += __shfl_xor(added, o);
-  if (lane == 0 && added) atomicAdd(a.alive, added);
-}
-
-// close level L: the nodes added during it form the next level
-__global__ void k_cell_level_advance(CellArgs a) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.n_prob) return;
-  a.lvl[p] = a.lvl[a.n_prob + p];
-  a.lvl[a.n_prob + p] = a.lvl[2 * a.n_prob + p];
+  if (__lane_id() == 0 && added) atomicAdd(a.alive, added);
 }
 
 __global__ void k_cell_zero(int32_t* x) { *x = 0; }
@@ -401,7 +457,7 @@ struct CellPlan {
   int fields[2] = {0, 0};
   bool slow = false;
   size_t off_tab = 0, off_W = 0, off_best = 0, off_ctl = 0, off_src = 0, off_act = 0,
-         off_key = 0, off_list = 0, off_hop = 0, off_bfs = 0, off_lvl = 0, total = 0;
+         off_key = 0, off_list = 0, off_hop = 0, off_bfs = 0, off_bid = 0, total = 0;
 };
 
 int cell_plan(const chert_cache_desc* d, int64_t n_classes, const chert_cell_grid* g,
@@ -468,10 +524,9 @@ int cell_plan(const chert_cache_desc* d, int64_t n_classes, const chert_cell_gri
   off += al256((size_t)2 * n_classes * n_classes * s2 * sizeof(double));
   P->off_best = off;
   if (P->slow) off += al256((size_t)n_classes * s2 * sizeof(int32_t));
-  P->off_ctl = off;  // count[2], err, alive, stats[3], wmin[2], minkey[2][P], lvl[3][P]
-  off += al256(256 + (size_t)2 * P->n_prob * sizeof(unsigned long long));
-  P->off_lvl = off;
-  off += al256((size_t)3 * P->n_prob * sizeof(int32_t));
+  P->off_ctl = off;  // count[2], err, alive, stats[3], wmin[2], minkey[3][P], bnd, cnt
+  off += al256(256 + (size_t)3 * P->n_prob * sizeof(unsigned long long) +
+               (size_t)6 * P->n_prob * sizeof(int32_t));
   P->off_src = off;
   off += al256((size_t)n_src * sizeof(int64_t));
   P->off_act = off;
@@ -483,6 +538,8 @@ int cell_plan(const chert_cache_desc* d, int64_t n_classes, const chert_cell_gri
   P->off_hop = off;
   off += al256((size_t)P->n_prob * P->n * sizeof(int32_t));
   P->off_bfs = off;
+  off += al256((size_t)P->n_prob * P->n * sizeof(int32_t));
+  P->off_bid = off;
   off += al256((size_t)P->n_prob * P->n * sizeof(int32_t));
   P->total = off;
   return CHERT_OK;
@@ -590,12 +647,14 @@ extern "C" int chert_trace_cells(const chert_cache_desc* d, const void* cache_de
   double* wmin = (double*)(ctl + 48);
   a.wmin = wmin;
   a.minkey = (unsigned long long*)(ctl + 256);
-  a.lvl = (int32_t*)(ws + P.off_lvl);
+  a.bnd = (int32_t*)(a.minkey + 3 * (size_t)P.n_prob);
+  a.cnt = a.bnd + 3 * (size_t)P.n_prob;
   a.active = (int32_t*)(ws + P.off_act);
   a.key = (unsigned long long*)(ws + P.off_key);
   a.list = (int32_t*)(ws + P.off_list);
   a.hop = (int32_t*)(ws + P.off_hop);
   a.bfs = (int32_t*)(ws + P.off_bfs);
+  a.bid = (int32_t*)(ws + P.off_bid);
   a.bucket = o->bucket_width;
   a.tree_mask = 0;
   for (int fi = 0; fi < P.nfs; ++fi) {
@@ -648,18 +707,22 @@ extern "C" int chert_trace_cells(const chert_cache_desc* d, const void* cache_de
   // traveltime rounds, the host checking the round's list size every group
   const int64_t items = (int64_t)P.n_prob * P.C;
   const unsigned gsel = (unsigned)((items + 255) / 256 > 2048 ? 2048 : (items + 255) / 256);
-  const unsigned grelax = (unsigned)((items + kCellWaves - 1) / kCellWaves > 4096
-                                         ? 4096
-                                         : (items + kCellWaves - 1) / kCellWaves);
+  // waves per workgroup: the staged pair weights (ns^2 doubles per wave)
+  // within 64 KiB of LDS
+  const int ns = 4 * cn;
+  int wpb = (int)(65536 / ((size_t)ns * ns * sizeof(double)));
+  if (wpb > kCellWaves) wpb = kCellWaves;
+  if (wpb < 1) wpb = 1;
+  const size_t lds = (size_t)wpb * ns * ns * sizeof(double);
+  const unsigned grelax =
+      (unsigned)((items + wpb - 1) / wpb > 4096 ? 4096 : (items + wpb - 1) / wpb);
   int rounds = -1;
   for (int r = 0; r < P.max_rounds && rounds < 0;) {
     const int group = r < 16 ? 16 : 32;
     const int nb = r + group > P.max_rounds ? P.max_rounds - r : group;
     for (int q = 0; q < nb; ++q) {
-      if (a.bucket > 0.0)
-        CHERT_LAUNCH("k_cell_minkey", k_cell_minkey, dim3(gsel), dim3(256), 0, s, a, r + q);
       CHERT_LAUNCH("k_cell_select", k_cell_select, dim3(gsel), dim3(256), 0, s, a, r + q);
-      CHERT_LAUNCH("k_cell_relax", k_cell_relax, dim3(grelax), dim3(kCellThreads), 0, s, a,
+      CHERT_LAUNCH("k_cell_relax", k_cell_relax, dim3(grelax), dim3(64 * wpb), lds, s, a,
                    r + q);
     }
     r += nb;
@@ -673,20 +736,17 @@ extern "C" int chert_trace_cells(const chert_cache_desc* d, const void* cache_de
   }
   if (rounds < 0) return fail(CHERT_ERR_NO_CONVERGENCE, "round cap reached");
 
-  // predecessors and t*: one level per launch, the host checking every group
+  // predecessors and t*: one launch per level, the host checking every 8
   int levels = 0;
   if (a.tree_mask) {
     unsigned gx = (unsigned)(2048 / P.n_prob);
     if (gx < 1) gx = 1;
-    if (gx > 64) gx = 64;
-    bool done = false;
-    for (int Lv = 0; !done;) {
+    if (gx > 256) gx = 256;
+    for (int Lv = 0;;) {
       CHERT_LAUNCH("k_cell_zero", k_cell_zero, dim3(1), dim3(1), 0, s, a.alive);
-      for (int q = 0; q < 8; ++q, ++Lv) {
-        CHERT_LAUNCH("k_cell_level", k_cell_level, dim3(gx, (unsigned)P.n_prob),
-                     dim3(kCellThreads), 0, s, a, Lv);
-        CHERT_LAUNCH("k_cell_level_advance", k_cell_level_advance, dim3(gp), dim3(256), 0, s, a);
-      }
+      for (int q = 0; q < 8; ++q, ++Lv)
+        CHERT_LAUNCH("k_cell_level", k_cell_level, dim3(gx, (unsigned)P.n_prob), dim3(256), 0,
+                     s, a, Lv);
       int32_t alive = 0;
       e = hipMemcpyAsync(&alive, a.alive, sizeof(int32_t), hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -694,11 +754,10 @@ extern "C" int chert_trace_cells(const chert_cache_desc* d, const void* cache_de
       if (o->abort_flag_host && *o->abort_flag_host)
         return fail(CHERT_ERR_ABORTED, "aborted by the caller");
       if (alive == 0) {
-        done = true;
         levels = Lv;
-      } else if (Lv > P.n + 8) {
-        return fail(CHERT_ERR_HIP, "BFS did not end");
+        break;
       }
+      if (Lv > P.n + 16) return fail(CHERT_ERR_HIP, "BFS did not end");
     }
   }
   if (o->stats_host) {

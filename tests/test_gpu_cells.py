@@ -188,3 +188,25 @@ def test_errors_leave_outputs_untouched(G):
     t = out[0].cpu().numpy()
     assert t[0] == 0.0 and np.isfinite(t[mask.reshape(-1)]).all()
     assert np.isinf(t[~mask.reshape(-1)]).all()
+
+
+@pytest.mark.parametrize("bucket", [0.0, 16.0])
+def test_full_size_layered_network_bitwise(G, bucket):
+    """The benchmark's network: 80x40 cells of 5x5 intervals on the 5-layer
+    401x201 lattice at 5 m, qSV through an imported oracle cache, every
+    output bitwise against the oracle."""
+    import workloads as W
+    C = _C()
+    m = W.config2()
+    cls = np.stack([O.class_from_thomsen(*L.thomsen_args()) for L in m.layers])
+    f, s = O.build_cache_2d(cls, n_dirs=360, mode_mask=0b010)
+    desc = C.cache_desc(n_dirs=360, modes=(1,))
+    K = cls.shape[0]
+    cache = G.import_cache(f, s, desc, K)
+    cn = 5
+    ncx, ncz = (m.nx - 1) // cn, (m.nz - 1) // cn
+    g = G.trace_cells(cache, desc, K, ncx, ncz, cn, m.hx, m.hz, m.class_id, 1, m.sources,
+                      bucket_width=bucket)
+    o = O.trace_cells_2d(ncx, ncz, cn, m.hx, m.hz, m.class_id, f[:, 1], s[1], m.sources[0])
+    for key in KEYS:
+        assert np.array_equal(g[key][0], o[key]), key
