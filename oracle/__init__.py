@@ -73,6 +73,8 @@ def lib():
         L.orc_build_cache_slow_2d.argtypes = [P, l, i, u, i, P, P]
         L.orc_trace_cells_2d.argtypes = [l, l, i, d, d, P, l, i, i, P, P, P, P, P, l, i,
                                          P, P, P, P, P]
+        L.orc_trace_mspm_2d.argtypes = [l, l, i, d, d, P, P, l, i, i, i, l, i,
+                                        P, P, P, P, P, P]
         L.orc_slow_lookup.argtypes = [l, i, P, P, P, i, P, P, d, d, P]
         L.orc_trace_2d_slow.argtypes = [l, l, d, d, P, l, i, i, P, P, P, P, P, l, P, P, P, P, P]
         _lib = L
@@ -375,4 +377,28 @@ def trace_cells_2d(ncx, ncz, cn, hx, hz, class_id, f_mode, st_mode, src, samplin
                                   _p(out["predA"]), _p(out["tstar"]))
     if rc:
         raise ValueError(f"orc_trace_cells_2d failed rc={rc}")
+    return out
+
+
+def trace_mspm_2d(ncx, ncz, cn, hx, hz, class_id, classes, mode, src, reading=MEV,
+                  n_sweep=N_SWEEP, block=False):
+    """MSPM (Algorithm 1) on the cell network: corner quantities from fresh
+    solves at each segment's exact direction, non-corner nodes linearly
+    reconstructed from the corners of their edge.  Returns lattice-sized
+    tauR, tauI, predP, predA, tstar and n_solves (distinct solves)."""
+    NX, NZ, _ = cell_lattice(ncx, ncz, cn)
+    n = NX * NZ
+    cid = np.ascontiguousarray(class_id, dtype=np.int32).reshape(-1)
+    assert cid.size == n
+    cls = np.ascontiguousarray(np.atleast_2d(classes), dtype=np.float64)
+    out = {k: np.zeros(n) for k in ("tauR", "tauI", "tstar")}
+    out.update({k: np.zeros(n, np.int32) for k in ("predP", "predA")})
+    ns = ctypes.c_long(0)
+    rc = lib().orc_trace_mspm_2d(ncx, ncz, cn, hx, hz, _p(cid), _p(cls), cls.shape[0], mode,
+                                 reading, n_sweep, int(src), int(bool(block)), _p(out["tauR"]),
+                                 _p(out["tauI"]), _p(out["predP"]), _p(out["predA"]),
+                                 _p(out["tstar"]), ctypes.byref(ns))
+    if rc:
+        raise ValueError(f"orc_trace_mspm_2d failed rc={rc}")
+    out["n_solves"] = ns.value
     return out

@@ -1424,6 +1424,13 @@ typedef struct {
   double *L;             /* [side^2] segment length per offset */
   int32_t *colR;         /* ray-direction cache: [side^2] column; NULL otherwise */
   int32_t *best;         /* slowness-sampled cache: [K][side^2]; NULL otherwise */
+  /* MSPM (O-19): no cache; corner solves at the segment's exact direction */
+  int mspm;
+  const double *classes; /* [K][13] */
+  int mode, reading, n_sweep;
+  double hx, hz;
+  double *mV, *mA;       /* [K][side^2] memo of the fresh solves (canonical offsets) */
+  int32_t *mst;          /* status; -1: not solved yet */
 } cellnet_t;
 
 static int cell_is_node(const cellnet_t *g, long ix, long iz) {
@@ -1434,7 +1441,11 @@ static int cell_off(const cellnet_t *g, long dx, long dz) {
   return (int)((dz + g->cn) * g->side + (dx + g->cn));
 }
 
-static double cell_weight(const cellnet_t *g, int field, long i, long j) {
+static double mspm_weight(cellnet_t *g, int field, long c, long i, long j);
+
+/* Weight of segment i -> j of cell c (the cell matters only to MSPM). */
+static double cell_weight(cellnet_t *g, int field, long c, long i, long j) {
+  if (g->mspm) return mspm_weight(g, field, c, i, j);
   long dx = (j % g->NX) - (i % g->NX), dz = (j / g->NX) - (i / g->NX);
   int o = cell_off(g, dx, dz);
   long ki = g->cls[i], kj = g->cls[j];
@@ -1488,28 +1499,45 @@ static int cell_nodes(const cellnet_t *g, long c, long *v) {
   return n;
 }
 
-/* Neighbours of u: the other boundary nodes of every cell holding u (a node
- * shared by two cells along their common edge is listed twice; the two
- * copies are the same segment and carry the same weight). */
-static int cell_neighbours(const cellnet_t *g, long u, long *nb) {
+/* Neighbours of u: the other boundary nodes of every cell holding u, with
+ * that cell in nbc (a node shared by two cells along their common edge is
+ * listed twice; the two copies are the same segment and carry the same
+ * weight). */
+static int cell_neighbours(const cellnet_t *g, long u, long *nb, long *nbc) {
   long cs[4], v[64 * 4];
   int nc = cells_of(g, u, cs), n = 0;
   for (int a = 0; a < nc; ++a) {
     int m = cell_nodes(g, cs[a], v);
     for (int b = 0; b < m; ++b)
-      if (v[b] != u) nb[n++] = v[b];
+      if (v[b] != u) {
+        nbc[n] = cs[a];
+        nb[n++] = v[b];
+      }
   }
   return n;
 }
 
-static int cell_dijkstra(const cellnet_t *g, int field, long src, double *tau) {
+/* A cell whose boundary holds both nodes i and j. */
+static long common_cell(const cellnet_t *g, long i, long j) {
+  long cs[4];
+  int nc = cells_of(g, j, cs);
+  long ix = i % g->NX, iz = i / g->NX;
+  for (int a = 0; a < nc; ++a) {
+    long x0 = (cs[a] % g->ncx) * g->cn, z0 = (cs[a] / g->ncx) * g->cn;
+    if (ix >= x0 && ix <= x0 + g->cn && iz >= z0 && iz <= z0 + g->cn) return cs[a];
+  }
+  return -1;
+}
+
+static int cell_dijkstra(cellnet_t *g, int field, long src, double *tau) {
   long n = g->NX * g->NZ;
   for (long i = 0; i < n; ++i) tau[i] = INFINITY;
   char *done = (char *)calloc((size_t)n, 1);
   long *nb = (long *)malloc(sizeof(long) * 16 * 64);
+  long *nbc = (long *)malloc(sizeof(long) * 16 * 64);
   heap_t h = {0, 0, 0};
   int rc = 0;
-  if (!done || !nb) { rc = 1; goto out; }
+  if (!done || !nb || !nbc) { rc = 1; goto out; }
   tau[src] = 0.0;
   if (heap_push(&h, 0.0, src)) { rc = 1; goto out; }
   while (h.n > 0) {
@@ -1517,11 +1545,11 @@ static int cell_dijkstra(const cellnet_t *g, int field, long src, double *tau) {
     long u = it.node;
     if (done[u] || it.key != tau[u]) continue;
     done[u] = 1;
-    int m = cell_neighbours(g, u, nb);
+    int m = cell_neighbours(g, u, nb, nbc);
     for (int b = 0; b < m; ++b) {
       long v = nb[b];
       if (done[v]) continue;
-      double cand = tau[u] + cell_weight(g, field, u, v);
+      double cand = tau[u] + cell_weight(g, field, nbc[b], u, v);
       if (cand < tau[v]) {
         tau[v] = cand;
         if (heap_push(&h, cand, v)) { rc = 1; goto out; }
@@ -1531,6 +1559,7 @@ static int cell_dijkstra(const cellnet_t *g, int field, long src, double *tau) {
 out:
   free(done);
   free(nb);
+  free(nbc);
   free(h.a);
   return rc;
 }
@@ -1544,7 +1573,7 @@ out:
  * the heap whenever one of its nodes improves, so the marching ends at the
  * network's shortest-path traveltimes (the same fixed point as node
  * Dijkstra) whatever the order. */
-static int cell_block_march(const cellnet_t *g, int field, long src, double *tau) {
+static int cell_block_march(cellnet_t *g, int field, long src, double *tau) {
   long n = g->NX * g->NZ, nc = g->ncx * g->ncz;
   for (long i = 0; i < n; ++i) tau[i] = INFINITY;
   double *key = (double *)malloc(sizeof(double) * (size_t)nc);
@@ -1576,7 +1605,7 @@ static int cell_block_march(const cellnet_t *g, int field, long src, double *tau
         if (!isfinite(tau[v[a]])) continue;
         for (int b = 0; b < m; ++b) {
           if (a == b) continue;
-          double cand = tau[v[a]] + cell_weight(g, field, v[a], v[b]);
+          double cand = tau[v[a]] + cell_weight(g, field, c, v[a], v[b]);
           if (cand < tau[v[b]]) {
             tau[v[b]] = cand;
             improved[b] = 1;
@@ -1612,13 +1641,14 @@ out:
  * (tau_i + w_ij == tau_j), pred_j = the tight neighbour i with the smallest
  * (hop, node index); t* (field 0 only) folds the attenuation weights along
  * that tree from the source outwards. */
-static int cell_predecessors(const cellnet_t *g, int field, long src, const double *tau,
+static int cell_predecessors(cellnet_t *g, int field, long src, const double *tau,
                              int32_t *pred, double *tstar) {
   long n = g->NX * g->NZ;
   int32_t *hop = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
   long *order = (long *)malloc(sizeof(long) * (size_t)n);
   long *nb = (long *)malloc(sizeof(long) * 16 * 64);
-  if (!hop || !order || !nb) { free(hop); free(order); free(nb); return 1; }
+  long *nbc = (long *)malloc(sizeof(long) * 16 * 64);
+  if (!hop || !order || !nb || !nbc) { free(hop); free(order); free(nb); free(nbc); return 1; }
   for (long i = 0; i < n; ++i) {
     pred[i] = -1;
     hop[i] = -1;
@@ -1628,11 +1658,11 @@ static int cell_predecessors(const cellnet_t *g, int field, long src, const doub
   order[tail++] = src;
   while (head < tail) {
     long i = order[head++];
-    int m = cell_neighbours(g, i, nb);
+    int m = cell_neighbours(g, i, nb, nbc);
     for (int b = 0; b < m; ++b) {
       long j = nb[b];
       if (hop[j] >= 0 || !isfinite(tau[j])) continue;
-      if (tau[i] + cell_weight(g, field, i, j) == tau[j]) {
+      if (tau[i] + cell_weight(g, field, nbc[b], i, j) == tau[j]) {
         hop[j] = hop[i] + 1;
         order[tail++] = j;
       }
@@ -1640,11 +1670,11 @@ static int cell_predecessors(const cellnet_t *g, int field, long src, const doub
   }
   for (long t = 1; t < tail; ++t) {
     long j = order[t], bi = -1;
-    int m = cell_neighbours(g, j, nb);
+    int m = cell_neighbours(g, j, nb, nbc);
     for (int b = 0; b < m; ++b) {
       long i = nb[b];
       if (hop[i] < 0) continue;
-      if (!(tau[i] + cell_weight(g, field, i, j) == tau[j])) continue;
+      if (!(tau[i] + cell_weight(g, field, nbc[b], i, j) == tau[j])) continue;
       if (bi < 0 || hop[i] < hop[bi] || (hop[i] == hop[bi] && i < bi)) bi = i;
     }
     pred[j] = (int32_t)bi;
@@ -1654,12 +1684,34 @@ static int cell_predecessors(const cellnet_t *g, int field, long src, const doub
     tstar[src] = 0.0;
     for (long t = 1; t < tail; ++t) {
       long j = order[t];
-      tstar[j] = tstar[pred[j]] + cell_weight(g, 1, pred[j], j);
+      tstar[j] = tstar[pred[j]] + cell_weight(g, 1, common_cell(g, pred[j], j), pred[j], j);
     }
   }
   free(hop);
   free(order);
   free(nb);
+  free(nbc);
+  return 0;
+}
+
+/* Both fields of one source on a network (outputs NULL to skip); t and p
+ * are lattice-sized scratch. */
+static int cell_fields(cellnet_t *g, long src, int block, double *t, int32_t *p,
+                       double *tauR, double *tauI, int32_t *predP, int32_t *predA,
+                       double *tstar) {
+  long n = g->NX * g->NZ;
+  for (int field = 0; field < 2; ++field) {
+    double *out_t = field ? tauI : tauR;
+    int32_t *out_p = field ? predA : predP;
+    double *ts = field ? NULL : tstar;
+    if (!out_t && !out_p && !ts) continue;
+    if (block ? cell_block_march(g, field, src, t) : cell_dijkstra(g, field, src, t)) return 2;
+    if (out_p || ts) {
+      if (cell_predecessors(g, field, src, t, p, ts)) return 2;
+      if (out_p) memcpy(out_p, p, sizeof(int32_t) * (size_t)n);
+    }
+    if (out_t) memcpy(out_t, t, sizeof(double) * (size_t)n);
+  }
   return 0;
 }
 
@@ -1707,22 +1759,147 @@ int orc_trace_cells_2d(long ncx, long ncz, int cn, double hx, double hz,
     if (!g.best) { rc = 2; goto out; }
     orc_slow_lookup(K, n_cols, RX, RZ, st, n_o, ox, oz, hx, hz, g.best);
   }
-  for (int field = 0; field < 2; ++field) {
-    double *out_t = field ? tauI : tauR;
-    int32_t *out_p = field ? predA : predP;
-    double *ts = field ? NULL : tstar;
-    if (!out_t && !out_p && !ts) continue;
-    if (block ? cell_block_march(&g, field, src, t) : cell_dijkstra(&g, field, src, t)) {
-      rc = 2;
-      goto out;
-    }
-    if (out_p || ts) {
-      if (cell_predecessors(&g, field, src, t, p, ts)) { rc = 2; goto out; }
-      if (out_p) memcpy(out_p, p, sizeof(int32_t) * (size_t)n);
-    }
-    if (out_t) memcpy(out_t, t, sizeof(double) * (size_t)n);
-  }
+  rc = cell_fields(&g, src, block, t, p, tauR, tauI, predP, predA, tstar);
 out:
   free(ox); free(oz); free(t); free(p); free(g.L); free(g.colR); free(g.best);
+  return rc;
+}
+
+
+/* ------------------------------------------------------------------------ */
+/* O-19  MSPM (Algorithm 1) on the cell network: no cache.  A segment's     */
+/*       ray quantities at a cell corner come from a fresh solve at the     */
+/*       segment's exact direction with the corner's class; at a node       */
+/*       between two corners they are reconstructed from those corners      */
+/* ------------------------------------------------------------------------ */
+
+/* One fresh solve at global ray angle psi (eqs 9-11 through the sweep and
+ * bisection of O-5): V, A and the status rules of cache entries. */
+static int solve_angle_fresh(const double *cls, int mode, int reading, int n_sweep,
+                             double psi, double *V, double *A) {
+  medium_t m;
+  load_medium(cls, &m);
+  int fluid = (mode != ORC_QP) && (cls[3] == 0.0 || (mode == ORC_QSH && cls[4] == 0.0));
+  if (fluid) return ORC_ST_FLUID;
+  sample_t *tab = (sample_t *)malloc(sizeof(sample_t) * (size_t)n_sweep);
+  if (!tab) return ORC_ST_NO_BRACKET;
+  sweep(&m, mode, reading, n_sweep, tab);
+  entry_t e;
+  int st = solve_direction(&m, mode, reading, n_sweep, tab, wrap_pi(psi - m.tilt), &e);
+  free(tab);
+  if (st & ORC_ST_NO_BRACKET) return st;
+  if (!(e.A >= 0.0) || !isfinite(e.V) || !(e.V > 0.0)) st |= ORC_ST_NONPHYS;
+  if (!(e.res <= ORC_RESID_TOL)) st |= ORC_ST_NOCONV;
+  *V = e.V;
+  *A = e.A;
+  return st;
+}
+
+/* The canonical one of offsets o and -o: direction angle in [0, pi). */
+static int mspm_canon(const cellnet_t *g, long dx, long dz) {
+  if (!(dx > 0 || (dx == 0 && dz > 0))) {
+    dx = -dx;
+    dz = -dz;
+  }
+  return cell_off(g, dx, dz);
+}
+
+/* Corner quantities of class k along canonical offset o (a reversed
+ * segment has the same ray quantities).  Each (class, offset) pair is
+ * solved once and reused: the solve is a pure function of them, so this
+ * changes no value, only the oracle's run time. */
+static int mspm_corner(cellnet_t *g, long k, int o, double *V, double *A) {
+  long idx = k * g->side * g->side + o;
+  if (g->mst[idx] < 0) {
+    int dx = o % g->side - g->cn, dz = o / g->side - g->cn;
+    double v = NAN, a = NAN;
+    g->mst[idx] = solve_angle_fresh(g->classes + 13 * k, g->mode, g->reading, g->n_sweep,
+                                    atan2(dx * g->hx, dz * g->hz), &v, &a);
+    g->mV[idx] = v;
+    g->mA[idx] = a;
+  }
+  *V = g->mV[idx];
+  *A = g->mA[idx];
+  return g->mst[idx];
+}
+
+/* Quantities of a node of cell c along canonical offset o: its own at a
+ * corner; between corners c1 and c2 of its edge, at fraction t of the edge
+ * from c1, q = q1 + t (q2 - q1) for V and A (linear reconstruction). */
+static int mspm_node(cellnet_t *g, long c, long node, int o, double *V, double *A) {
+  long x0 = (c % g->ncx) * g->cn, z0 = (c / g->ncx) * g->cn;
+  long lx = node % g->NX - x0, lz = node / g->NX - z0;
+  int cx = (lx == 0 || lx == g->cn), cz = (lz == 0 || lz == g->cn);
+  if (cx && cz) return mspm_corner(g, g->cls[node], o, V, A);
+  long c1, c2;
+  double t;
+  if (cz) { /* on a horizontal edge */
+    c1 = x0 + g->NX * (z0 + lz);
+    c2 = x0 + g->cn + g->NX * (z0 + lz);
+    t = (double)lx / (double)g->cn;
+  } else { /* on a vertical edge */
+    c1 = x0 + lx + g->NX * z0;
+    c2 = x0 + lx + g->NX * (z0 + g->cn);
+    t = (double)lz / (double)g->cn;
+  }
+  double V1, A1, V2, A2;
+  int s1 = mspm_corner(g, g->cls[c1], o, &V1, &A1);
+  int s2 = mspm_corner(g, g->cls[c2], o, &V2, &A2);
+  *V = V1 + t * (V2 - V1);
+  *A = A1 + t * (A2 - A1);
+  return s1 | s2;
+}
+
+static double mspm_weight(cellnet_t *g, int field, long c, long i, long j) {
+  long dx = (j % g->NX) - (i % g->NX), dz = (j / g->NX) - (i / g->NX);
+  int o = mspm_canon(g, dx, dz);
+  double Vi, Ai, Vj, Aj;
+  int si = mspm_node(g, c, i, o, &Vi, &Ai);
+  int sj = mspm_node(g, c, j, o, &Vj, &Aj);
+  const int bad = ORC_ST_NO_BRACKET | ORC_ST_FLUID | ORC_ST_NONPHYS | ORC_ST_NOCONV;
+  if ((si & bad) || (sj & bad)) return INFINITY;
+  double L = g->L[cell_off(g, dx, dz)];
+  if (field == 0) return L / (0.5 * (Vi + Vj));
+  return L * (0.5 * (Ai + Aj));
+}
+
+/* MSPM trace of one source for one mode on the cell network of the class
+ * map (classes [K][13], reading MEV/OEV, n_sweep samples per solve); the
+ * same outputs and predecessor rule as orc_trace_cells_2d.  *n_solves
+ * (nullable) receives the number of distinct (class, direction) solves. */
+int orc_trace_mspm_2d(long ncx, long ncz, int cn, double hx, double hz,
+                      const int32_t *class_id, const double *classes, long K, int mode,
+                      int reading, int n_sweep, long src, int block, double *tauR,
+                      double *tauI, int32_t *predP, int32_t *predA, double *tstar,
+                      long *n_solves) {
+  if (ncx < 1 || ncz < 1 || cn < 1 || cn > 16 || !class_id || n_sweep < 8) return 1;
+  cellnet_t g = {.ncx = ncx, .ncz = ncz, .NX = ncx * cn + 1, .NZ = ncz * cn + 1, .cn = cn,
+                 .side = 2 * cn + 1, .cls = class_id, .K = K, .mspm = 1, .classes = classes,
+                 .mode = mode, .reading = reading, .n_sweep = n_sweep, .hx = hx, .hz = hz};
+  long n = g.NX * g.NZ;
+  if (src < 0 || src >= n || !cell_is_node(&g, src % g.NX, src / g.NX)) return 1;
+  int n_o = g.side * g.side;
+  double *t = (double *)malloc(sizeof(double) * (size_t)n);
+  int32_t *p = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  g.L = (double *)malloc(sizeof(double) * n_o);
+  g.mV = (double *)malloc(sizeof(double) * (size_t)K * n_o);
+  g.mA = (double *)malloc(sizeof(double) * (size_t)K * n_o);
+  g.mst = (int32_t *)malloc(sizeof(int32_t) * (size_t)K * n_o);
+  int rc = 0;
+  if (!t || !p || !g.L || !g.mV || !g.mA || !g.mst) { rc = 2; goto out; }
+  for (int dz = -cn; dz <= cn; ++dz)
+    for (int dx = -cn; dx <= cn; ++dx) {
+      double ex = dx * hx, ez = dz * hz;
+      g.L[cell_off(&g, dx, dz)] = sqrt(ex * ex + ez * ez);
+    }
+  for (long q = 0; q < K * n_o; ++q) g.mst[q] = -1;
+  rc = cell_fields(&g, src, block, t, p, tauR, tauI, predP, predA, tstar);
+  if (n_solves) {
+    long c = 0;
+    for (long q = 0; q < K * n_o; ++q) c += g.mst[q] >= 0;
+    *n_solves = c;
+  }
+out:
+  free(t); free(p); free(g.L); free(g.mV); free(g.mA); free(g.mst);
   return rc;
 }
