@@ -531,6 +531,29 @@ int chert_trace_cells(const chert_cache_desc *d, const void *cache_dev, int64_t 
                       int32_t *pred_a_dev, void *workspace_dev, size_t workspace_bytes,
                       void *stream);
 
+/* MSPM baseline (Algorithm 1; Table A-1) on the same cell network, with no
+ * cache: each round's visited cells regenerate their local tables, i.e.
+ * every corner of every visited cell is solved afresh (theta_R sweep of
+ * n_sweep samples, then one root search per canonical segment direction:
+ * the exact direction of the segment's offset or its reverse, whichever has
+ * angle in [0, pi)) with the corner's class and the chosen kernel (MEV or
+ * OEV).  A node between two corners of its edge takes V and A reconstructed
+ * linearly from those corners at its fraction t of the edge,
+ * x = x1 + t (x2 - x1) (the paper leaves the rule open); weights then follow
+ * eqs 28-30.  classes_dev: [n_classes] device classes; the class map of g
+ * indexes them.  Outputs, options and errors as chert_trace_cells; the
+ * predecessors, t* and the ordering scale read a per-class table solved
+ * once per call with the same kernel code (the same values).  stats_host
+ * also gets edge_relaxations[1] = corner solves of the rounds. */
+size_t chert_trace_mspm_workspace_bytes(int64_t n_classes, const chert_cell_grid *g,
+                                        int32_t n_src, const chert_trace_opts *o);
+int chert_trace_mspm(const chert_class *classes_dev, int64_t n_classes,
+                     const chert_cell_grid *g, int32_t mode, int32_t kernel, int32_t n_sweep,
+                     const int64_t *src_nodes_host, int32_t n_src, const chert_trace_opts *o,
+                     double *tau_r_dev, double *tau_i_dev, double *tstar_dev,
+                     int32_t *pred_p_dev, int32_t *pred_a_dev, void *workspace_dev,
+                     size_t workspace_bytes, void *stream);
+
 /* Raypath (eqs 25, 33-34): follow pred from rcv back to src and write the
  * node sequence src ... rcv into path_out.  Host, synchronous.
  * *path_len receives the length (also on CAPACITY, so the caller can retry).

@@ -46,6 +46,7 @@ EXPORTS = (
     "chert_trace_graph_destroy", "chert_trace_autotune_workspace_bytes", "chert_trace_autotune",
     "chert_star_3d", "chert_build_cache_noalloc", "chert_build_cache_noalloc_max_bytes",
     "chert_trace_cells_workspace_bytes", "chert_trace_cells",
+    "chert_trace_mspm_workspace_bytes", "chert_trace_mspm",
 )
 WARM_NSTATS = 10
 # parameter blocks of the surrogate, in their order in the parameter vector
@@ -216,6 +217,10 @@ def lib():
         L.chert_trace_cells_workspace_bytes.argtypes = [P, i64, P, i32, P]
         L.chert_trace_cells_workspace_bytes.restype = sz
         L.chert_trace_cells.argtypes = [P, P, i64, P, i32, P, i32, P, P, P, P, P, P, P, sz, P]
+        L.chert_trace_mspm_workspace_bytes.argtypes = [i64, P, i32, P]
+        L.chert_trace_mspm_workspace_bytes.restype = sz
+        L.chert_trace_mspm.argtypes = [P, i64, P, i32, i32, i32, P, i32, P, P, P, P, P, P, P,
+                                       sz, P]
         _lib = L
     return _lib
 
@@ -445,6 +450,22 @@ def chert_trace_cells(desc, cache_dev, n_classes, grid, mode, src_nodes: Sequenc
     ws = workspace_dev.numel() * workspace_dev.element_size() if workspace_dev is not None else 0
     _check(lib().chert_trace_cells(
         ctypes.byref(desc), _ptr(cache_dev), n_classes, ctypes.byref(grid), mode,
+        src.ctypes.data, int(src.size), ctypes.byref(opts), _ptr(tau_r), _ptr(tau_i),
+        _ptr(tstar), _ptr(pred_p), _ptr(pred_a), _ptr(workspace_dev), ws, _stream(stream)))
+
+
+def chert_trace_mspm_workspace_bytes(n_classes, grid, n_src, opts):
+    return int(lib().chert_trace_mspm_workspace_bytes(n_classes, ctypes.byref(grid), n_src,
+                                                      ctypes.byref(opts)))
+
+
+def chert_trace_mspm(classes_dev, n_classes, grid, mode, src_nodes: Sequence[int], opts,
+                     tau_r=None, tau_i=None, tstar=None, pred_p=None, pred_a=None,
+                     workspace_dev=None, kernel=KERNEL_MEV, n_sweep=1440, stream=None):
+    src = np.ascontiguousarray(np.asarray(src_nodes, dtype=np.int64).reshape(-1))
+    ws = workspace_dev.numel() * workspace_dev.element_size() if workspace_dev is not None else 0
+    _check(lib().chert_trace_mspm(
+        _ptr(classes_dev), n_classes, ctypes.byref(grid), mode, kernel, n_sweep,
         src.ctypes.data, int(src.size), ctypes.byref(opts), _ptr(tau_r), _ptr(tau_i),
         _ptr(tstar), _ptr(pred_p), _ptr(pred_a), _ptr(workspace_dev), ws, _stream(stream)))
 

@@ -599,6 +599,86 @@ __global__ void __launch_bounds__(kNodeThreads) k_build_fused(SolveArgs a, const
   }
 }
 
+// MSPM's local tables (Algorithm 1): for each job -- a class -- a fresh
+// theta_R sweep into LDS, then one solve per target global ray angle.  No
+// cache and nothing kept between calls: every call pays for its sweeps.
+// Outputs V, A and the status of each (job, target), with the status rules
+// of cache entries (NaN quantities where there is no usable root).
+__global__ void __launch_bounds__(64) k_mspm_solve(SolveArgs a, const int32_t* job_class,
+                                                   const int32_t* n_jobs_dev, int n_jobs_mul,
+                                                   int64_t n_jobs_fixed, const double* psi,
+                                                   int n_tgt, double* V, double* A,
+                                                   int32_t* st) {
+  extern __shared__ double2 tab[];
+  __shared__ int s_br[64 * kMaxBr];
+  const int64_t n = n_jobs_dev ? (int64_t)(*n_jobs_dev) * n_jobs_mul : n_jobs_fixed;
+  const int mode = a.modes[0];
+  for (int64_t q = blockIdx.x; q < n; q += gridDim.x) {
+    const int64_t k = job_class ? (int64_t)job_class[q] : q;
+    const chert_class c = a.classes[k];
+    const int32_t blocked = class_block(c, mode);
+    double* Vq = V + q * n_tgt;
+    double* Aq = A + q * n_tgt;
+    int32_t* Sq = st + q * n_tgt;
+    if (blocked) {
+      for (int t = threadIdx.x; t < n_tgt; t += blockDim.x) {
+        Vq[t] = NAN;
+        Aq[t] = NAN;
+        Sq[t] = blocked;
+      }
+      continue;  // block-uniform
+    }
+    const Medium m = load_medium(c);
+    __syncthreads();  // the previous job's solves are done with tab
+    for (int j = threadIdx.x; j < a.n_sweep; j += blockDim.x) {
+      const double thR = (j + 0.5) * (kTwoPi / a.n_sweep);
+      double thI, sr, cr;
+      sincos(thR, &sr, &cr);
+      double2 out = make_double2(0.0, NAN);
+      if (theta_imag_sc(m, mode, a.kernel, sr, cr, &thI)) {
+        const double ps = ray_angle_sc(m, mode, a.kernel, sr, cr, thI);
+        if (isfinite(ps)) out = make_double2(thI, ps);
+      }
+      tab[j] = out;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < n_tgt; t += blockDim.x) {
+      Entry best{};
+      int32_t s = solve_dir(a, m, mode, FullTable{tab, a.n_sweep}, wrap_pi(psi[t] - m.tilt),
+                            s_br + threadIdx.x * kMaxBr, &best);
+      if ((s & (CHERT_ST_NO_BRACKET | CHERT_ST_FLUID)) || (s == CHERT_ST_NONPHYS && isnan(best.V))) {
+        Vq[t] = NAN;
+        Aq[t] = NAN;
+      } else {
+        if (!(best.res <= a.resid_tol)) s |= CHERT_ST_NOCONV;
+        Vq[t] = best.V;
+        Aq[t] = best.A;
+      }
+      Sq[t] = s;
+    }
+  }
+}
+
+int enqueue_mspm_solve(const chert_class* classes_dev, int mode, int kernel, int n_sweep,
+                       const int32_t* job_class, const int32_t* n_jobs_dev, int n_jobs_mul,
+                       int64_t n_jobs_fixed, int64_t grid, const double* psi_dev, int n_tgt,
+                       double* V, double* A, int32_t* st, hipStream_t s) {
+  SolveArgs so{};
+  so.modes[0] = mode;
+  so.n_modes = 1;
+  so.classes = classes_dev;
+  so.kernel = kernel;
+  so.n_sweep = n_sweep;
+  so.resid_tol = 1e-9;
+  so.newton_iters = 12;
+  so.bisect_iters = 200;
+  const unsigned g = (unsigned)(grid < 1 ? 1 : (grid > 65535 ? 65535 : grid));
+  CHERT_LAUNCH("k_mspm_solve", k_mspm_solve, dim3(g), dim3(64),
+               (size_t)n_sweep * sizeof(double2), s, so, job_class, n_jobs_dev, n_jobs_mul,
+               n_jobs_fixed, psi_dev, n_tgt, V, A, st);
+  return CHERT_OK;
+}
+
 // ---------------------------------------------------------------- warm start
 // Surrogate-started solve: the MLP (mlp.h) predicts (theta_R, theta_I) for
 // each solved direction, an FP64 Newton iteration polishes it, and the root

@@ -115,7 +115,7 @@ struct CellArgs {
   unsigned long long* minkey;  // [3][P]: round r reads slot r % 3
   int32_t* list;               // [P C] selected (problem, cell) items
   int32_t* count;              // [2] (round parity)
-  unsigned long long* stats;   // visits, pair relaxations, passes
+  unsigned long long* stats;   // visits, pair relaxations, passes, MSPM corner jobs
   const double* wmin;          // [2]
   double bucket;               // ordering width in units of wmin (0: none)
   // level phase
@@ -128,7 +128,102 @@ struct CellArgs {
   int32_t* pred[2];    // per field slot, rows [n_src][n] (nullable)
   double* tstar;       // rows [n_src][n] for the propagation slot (nullable)
   int tree_mask;       // bit fi: problems of field slot fi need the tree
+  // MSPM (no cache): corner tables [row][n_canon] of V, A, status per
+  // canonical segment offset; the rounds read one row per visited cell
+  // corner (row it * 4 + corner of the round's list), the tree phase one row
+  // per class
+  int mspm;
+  int n_canon;
+  const int32_t* canon;  // [side^2] canonical offset index (-1: centre)
+  const double* L;       // [side^2] segment lengths
+  const double *tV, *tA;
+  const int32_t* tS;     // visit tables
+  const double *kV, *kA;
+  const int32_t* kS;     // class table
+  int32_t* job_class;    // [4 P C] class of each (visit, corner) solve job
 };
+
+// MSPM quantities of the node at local (lx, lz) of a cell along canonical
+// offset ci: at a corner its own row; between the corners q1, q2 of its
+// edge, at fraction t of the edge from q1, x = x1 + t (x2 - x1) for V and A.
+// Corner q: 0 = (0, 0), 1 = (cn, 0), 2 = (0, cn), 3 = (cn, cn); row[q] is
+// the table row of corner q.
+__device__ __forceinline__ int32_t mspm_node(int cn, const int64_t* row, int lx, int lz, int ci,
+                                             const double* V, const double* A, const int32_t* S,
+                                             double* v, double* at) {
+  const bool ex = lx == 0 || lx == cn, ez = lz == 0 || lz == cn;
+  if (ex && ez) {
+    const int64_t r = row[(lx == cn) + 2 * (lz == cn)] + ci;
+    *v = V[r];
+    *at = A[r];
+    return S[r];
+  }
+  int q1, q2;
+  double t;
+  if (ez) {  // horizontal edge: corners (0, lz) and (cn, lz)
+    q1 = 2 * (lz == cn);
+    q2 = q1 + 1;
+    t = (double)lx / (double)cn;
+  } else {   // vertical edge: corners (lx, 0) and (lx, cn)
+    q1 = (lx == cn);
+    q2 = q1 + 2;
+    t = (double)lz / (double)cn;
+  }
+  const int64_t r1 = row[q1] + ci, r2 = row[q2] + ci;
+  const double v1 = V[r1], v2 = V[r2], a1 = A[r1], a2 = A[r2];
+  *v = v1 + t * (v2 - v1);
+  *at = a1 + t * (a2 - a1);
+  return S[r1] | S[r2];
+}
+
+// MSPM weight of the segment from local (ax, az) to (bx, bz) of one cell
+// (eqs 28-30 with the reconstructed end quantities); +inf if unusable
+__device__ __forceinline__ double mspm_w(const CellArgs& a, int f, const int64_t* row, int ax,
+                                         int az, int bx, int bz, const double* V, const double* A,
+                                         const int32_t* S) {
+  const int cn = a.cn;
+  const int off = (bz - az + cn) * a.side + (bx - ax + cn);
+  const int ci = a.canon[off];
+  double va, aa, vb, ab;
+  const int32_t sa = mspm_node(cn, row, ax, az, ci, V, A, S, &va, &aa);
+  const int32_t sb = mspm_node(cn, row, bx, bz, ci, V, A, S, &vb, &ab);
+  const int32_t bad = CHERT_ST_NO_BRACKET | CHERT_ST_FLUID | CHERT_ST_NONPHYS | CHERT_ST_NOCONV;
+  if ((sa | sb) & bad) return INFINITY;
+  return f == 0 ? a.L[off] / (0.5 * (va + vb)) : a.L[off] * (0.5 * (aa + ab));
+}
+
+// Weight of segment i -> j of cell c (field f): the class-pair table of a
+// cached network, or MSPM's reconstruction from the class table.
+__device__ __forceinline__ double seg_weight(const CellArgs& a, int f, int c, int64_t i,
+                                             int64_t j) {
+  const int cn = a.cn;
+  const int ix = (int)(i % a.NX), iz = (int)(i / a.NX), jx = (int)(j % a.NX), jz = (int)(j / a.NX);
+  if (!a.mspm) {
+    const int64_t s2 = (int64_t)a.side * a.side;
+    const int off = (jz - iz + cn) * a.side + (jx - ix + cn);
+    return a.W[(int64_t)f * a.K * a.K * s2 + ((int64_t)a.cls[i] * a.K + a.cls[j]) * s2 + off];
+  }
+  const int x0 = (c % a.ncx) * cn, z0 = (c / a.ncx) * cn;
+  int64_t row[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t node = (int64_t)(x0 + (q & 1) * cn) + (int64_t)a.NX * (z0 + (q >> 1) * cn);
+    row[q] = (int64_t)a.cls[node] * a.n_canon;
+  }
+  return mspm_w(a, f, row, ix - x0, iz - z0, jx - x0, jz - z0, a.kV, a.kA, a.kS);
+}
+
+// a cell whose boundary holds both lattice nodes i and j
+__device__ __forceinline__ int common_cell(const CellArgs& a, int64_t i, int64_t j) {
+  int cs[4];
+  const int nc = cells_of((int)(j % a.NX), (int)(j / a.NX), a.cn, a.ncx, a.ncz, cs);
+  const int ix = (int)(i % a.NX), iz = (int)(i / a.NX);
+  for (int q = 0; q < nc; ++q) {
+    const int x0 = (cs[q] % a.ncx) * a.cn, z0 = (cs[q] / a.ncx) * a.cn;
+    if (ix >= x0 && ix <= x0 + a.cn && iz >= z0 && iz <= z0 + a.cn) return cs[q];
+  }
+  return cs[0];
+}
 
 __device__ __forceinline__ double* tau_row(const CellArgs& a, int p) {
   const int fi = p / a.n_src, s = p - fi * a.n_src;
@@ -166,7 +261,7 @@ __global__ void k_cell_fill(CellArgs a) {
   }
   if (p == 0 && blockIdx.x == 0 && threadIdx.x < 8) {
     if (threadIdx.x < 2) a.count[threadIdx.x] = 0;
-    if (threadIdx.x < 3) a.stats[threadIdx.x] = 0;
+    if (threadIdx.x < 4) a.stats[threadIdx.x] = 0;
     if (threadIdx.x == 3) *a.alive = 0;
   }
 }
@@ -268,7 +363,7 @@ __global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) 
     const int c = (int)(item - (int64_t)p * a.C);
     const int cx = c % a.ncx, cz = c / a.ncx;
     double* tau = tau_row(a, p);
-    const double* W = a.W + (int64_t)a.field_of[p / a.n_src] * K * K * s2;
+    const double* W = a.W ? a.W + (int64_t)a.field_of[p / a.n_src] * K * K * s2 : nullptr;
     const int gx = cx * cn + lx, gz = cz * cn + lz;
     const int64_t node = (int64_t)gx + (int64_t)a.NX * gz;
     int k = 0;
@@ -280,7 +375,18 @@ __global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) 
     // stage w(a -> lane) for every slot a (the diagonal is never read),
     // eight loads in flight per lane; slot a's class and position come from
     // lane a
-    {
+    if (a.mspm) {  // this visit's corner rows (solved for it this round)
+      const int f = a.field_of[p / a.n_src];
+      int64_t row[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) row[q] = ((int64_t)it * 4 + q) * a.n_canon;
+      for (int sa = 0; sa < ns; ++sa) {
+        const int ax = __builtin_amdgcn_readlane(lx, sa);
+        const int az = __builtin_amdgcn_readlane(lz, sa);
+        if (lane < ns && lane != sa)
+          wl[sa * ns + lane] = mspm_w(a, f, row, ax, az, lx, lz, a.tV, a.tA, a.tS);
+      }
+    } else {
       const double* Wk = W + (int64_t)k * s2;  // column class = this lane's
       for (int sa0 = 0; sa0 < ns; sa0 += 8) {
         double w8[8];
@@ -383,12 +489,9 @@ __global__ void __launch_bounds__(256) k_cell_level(CellArgs a, int L) {
     a.cnt[((L + 1) % 3) * P + p] = 0;
   }
   int32_t* cnt = a.cnt + (L % 3) * P + p;
-  const int cn = a.cn, ns = 4 * cn, side = a.side, K = a.K;
+  const int cn = a.cn, ns = 4 * cn;
   const int per = 4 * ns;  // (cell, slot) triples per node
-  const int64_t s2 = (int64_t)side * side;
   const int f = a.field_of[fi];
-  const double* W = a.W + (int64_t)f * K * K * s2;
-  const double* WI = a.W + (int64_t)K * K * s2;
   const double* tau = a.tau[fi] + (int64_t)s * a.n;
   int32_t* hop = a.hop + (int64_t)p * a.n;
   int32_t* bfs = a.bfs + (int64_t)p * a.n;
@@ -411,16 +514,13 @@ __global__ void __launch_bounds__(256) k_cell_level(CellArgs a, int L) {
     const int vx = (cs[q] % a.ncx) * cn + lx, vz = (cs[q] / a.ncx) * cn + lz;
     const int64_t v = (int64_t)vx + (int64_t)a.NX * vz;
     if (v == j) continue;
-    const int kj = a.cls[j], kv = a.cls[v];
     const double tj = tau[j], tv = tau[v];
     const int hv = hop[v];
     if (L > 0 && hv == L - 1) {  // v -> j tight?
-      const int off = (jz - vz + cn) * side + (jx - vx + cn);
-      if (tv + W[((int64_t)kv * K + kj) * s2 + off] == tj) atomicMin(&bid[j], (int)v);
+      if (tv + seg_weight(a, f, cs[q], v, j) == tj) atomicMin(&bid[j], (int)v);
     }
     if (hv == -1 && tv < INFINITY) {  // j -> v tight?
-      const int off = (vz - jz + cn) * side + (vx - jx + cn);
-      if (tj + W[((int64_t)kj * K + kv) * s2 + off] == tv && atomicCAS(&hop[v], -1, L + 1) == -1) {
+      if (tj + seg_weight(a, f, cs[q], j, v) == tv && atomicCAS(&hop[v], -1, L + 1) == -1) {
         bfs[end + atomicAdd(cnt, 1)] = (int32_t)v;
         ++added;
       }
@@ -435,12 +535,7 @@ __global__ void __launch_bounds__(256) k_cell_level(CellArgs a, int L) {
       // in bounds
       if (b == 0x7fffffff) continue;
       if (pred) pred[j] = b;
-      if (ts) {
-        const int jx = (int)(j % a.NX), jz = (int)(j / a.NX);
-        const int ix = b % a.NX, iz = b / a.NX;
-        const int off = (jz - iz + cn) * side + (jx - ix + cn);
-        ts[j] = ts[b] + WI[((int64_t)a.cls[b] * K + a.cls[j]) * s2 + off];
-      }
+      if (ts) ts[j] = ts[b] + seg_weight(a, 1, common_cell(a, b, j), b, j);
     }
   }
   for (int o = 32; o > 0; o >>= 1) added += __shfl_xor(added, o);
@@ -451,25 +546,87 @@ __global__ void k_cell_zero(int32_t* x) { *x = 0; }
 
 // ---------------------------------------------------------------- plan ----
 
+// MSPM, round r: the class of each corner of each listed cell (the solve
+// jobs of this round's visits, job it * 4 + corner)
+__global__ void k_mspm_jobs(CellArgs a, int r) {
+  const int count = a.count[r & 1];
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < 4LL * count;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int it = (int)(t >> 2), q = (int)(t & 3);
+    const int64_t item = a.list[it];
+    const int c = (int)(item % a.C);
+    const int x0 = (c % a.ncx) * a.cn + (q & 1) * a.cn, z0 = (c / a.ncx) * a.cn + (q >> 1) * a.cn;
+    a.job_class[t] = a.cls[(int64_t)x0 + (int64_t)a.NX * z0];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.stats[3], 4ull * count);
+}
+
+// MSPM ordering scale: per field the smallest positive L / V and L A over
+// the class table (canonical segment lengths)
+__global__ void k_mspm_wmin(CellArgs a, const double* Lc, int64_t rows) {
+  double m0 = INFINITY, m1 = INFINITY;
+  const int32_t bad = CHERT_ST_NO_BRACKET | CHERT_ST_FLUID | CHERT_ST_NONPHYS | CHERT_ST_NOCONV;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < rows * a.n_canon;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    if (a.kS[t] & bad) continue;
+    const double l = Lc[t % a.n_canon];
+    const double w0 = l / a.kV[t], w1 = l * a.kA[t];
+    if (w0 > 0.0 && w0 < m0) m0 = w0;
+    if (w1 > 0.0 && w1 < m1) m1 = w1;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    m0 = fmin(m0, __shfl_xor(m0, o));
+    m1 = fmin(m1, __shfl_xor(m1, o));
+  }
+  double* wmin = const_cast<double*>(a.wmin);
+  if (__lane_id() == 0) {
+    if (m0 < INFINITY) atomicMin((unsigned long long*)&wmin[0], dbits(m0));
+    if (m1 < INFINITY) atomicMin((unsigned long long*)&wmin[1], dbits(m1));
+  }
+}
+
+// Where the segment weights come from: a cache (the cached network) or
+// MSPM's fresh corner solves.
+struct CellSrc {
+  bool mspm = false;
+  const chert_cache_desc* d = nullptr;
+  const void* cache_dev = nullptr;
+  const chert_class* classes_dev = nullptr;
+  int kernel = 0, n_sweep = 0;
+};
+
 struct CellPlan {
   int cn = 0, side = 0, NX = 0, NZ = 0, n_prob = 0, nfs = 0, max_rounds = 0, n_cols = 0;
+  int n_canon = 0;
   int64_t n = 0, C = 0, K = 0;
   int fields[2] = {0, 0};
   bool slow = false;
   size_t off_tab = 0, off_W = 0, off_best = 0, off_ctl = 0, off_src = 0, off_act = 0,
-         off_key = 0, off_list = 0, off_hop = 0, off_bfs = 0, off_bid = 0, total = 0;
+         off_key = 0, off_list = 0, off_hop = 0, off_bfs = 0, off_bid = 0, off_kt = 0,
+         off_vt = 0, off_jobs = 0, total = 0;
 };
 
-int cell_plan(const chert_cache_desc* d, int64_t n_classes, const chert_cell_grid* g,
-              int32_t mode, const int64_t* src, int32_t n_src, const chert_trace_opts* o,
-              CellPlan* P) {
-  if (!d || !g || !o) return fail(CHERT_ERR_INVALID_ARG, "null descriptor, grid or options");
-  chert_cache_layout lay;
-  int rc = chert_cache_layout_of(d, n_classes, &lay);
-  if (rc) return rc;
-  if (d->dim != 2) return fail(CHERT_ERR_INVALID_ARG, "cell networks are 2D");
-  if (mode < 0 || mode > 2 || !(d->mode_mask & (1u << mode)))
-    return fail(CHERT_ERR_INVALID_ARG, "mode not in the cache");
+int cell_plan(const CellSrc& w, int64_t n_classes, const chert_cell_grid* g, int32_t mode,
+              const int64_t* src, int32_t n_src, const chert_trace_opts* o, CellPlan* P) {
+  if (!g || !o) return fail(CHERT_ERR_INVALID_ARG, "null grid or options");
+  if (!w.mspm) {
+    const chert_cache_desc* d = w.d;
+    if (!d) return fail(CHERT_ERR_INVALID_ARG, "null descriptor");
+    chert_cache_layout lay;
+    int rc = chert_cache_layout_of(d, n_classes, &lay);
+    if (rc) return rc;
+    if (d->dim != 2) return fail(CHERT_ERR_INVALID_ARG, "cell networks are 2D");
+    if (mode < 0 || mode > 2 || !(d->mode_mask & (1u << mode)))
+      return fail(CHERT_ERR_INVALID_ARG, "mode not in the cache");
+    P->slow = d->sampling == CHERT_SAMPLE_SLOWNESS;
+    P->n_cols = d->n_subset ? d->n_subset : d->n_dirs;
+  } else {
+    if (mode < 0 || mode > 2) return fail(CHERT_ERR_INVALID_ARG, "mode must be 0..2");
+    if (w.kernel != CHERT_KERNEL_MEV && w.kernel != CHERT_KERNEL_OEV)
+      return fail(CHERT_ERR_INVALID_ARG, "kernel must be MEV or OEV");
+    if (w.n_sweep < 8 || w.n_sweep > kMaxSweep)
+      return fail(CHERT_ERR_INVALID_ARG, "n_sweep must be 8..4096");
+  }
   if (g->ncx < 1 || g->ncz < 1) return fail(CHERT_ERR_INVALID_ARG, "need at least one cell");
   if (g->cell_n < 1 || g->cell_n > kCellMaxN)
     return fail(CHERT_ERR_INVALID_ARG, "cell_n must be 1..16");
@@ -478,6 +635,7 @@ int cell_plan(const chert_cache_desc* d, int64_t n_classes, const chert_cell_gri
   if (!g->class_id_dev) return fail(CHERT_ERR_INVALID_ARG, "cell networks need a class map");
   P->cn = g->cell_n;
   P->side = 2 * P->cn + 1;
+  P->n_canon = 2 * P->cn * (P->cn + 1);
   const int64_t NX = (int64_t)g->ncx * P->cn + 1, NZ = (int64_t)g->ncz * P->cn + 1;
   if (NX * NZ >= 0x7fffffffLL) return fail(CHERT_ERR_INVALID_ARG, "lattice too large");
   P->NX = (int)NX;
@@ -488,8 +646,6 @@ int cell_plan(const chert_cache_desc* d, int64_t n_classes, const chert_cell_gri
   if (n_classes < 1) return fail(CHERT_ERR_INVALID_ARG, "need at least one class");
   if (n_classes * n_classes * P->side * P->side >= 0x7fffffffLL)
     return fail(CHERT_ERR_UNSUPPORTED, "class-pair table too large");
-  P->slow = d->sampling == CHERT_SAMPLE_SLOWNESS;
-  P->n_cols = d->n_subset ? d->n_subset : d->n_dirs;
   const uint32_t outs = o->outputs;
   if (outs == 0 || (outs & ~31u) || !(outs & (CHERT_OUT_TAU_R | CHERT_OUT_TAU_I)))
     return fail(CHERT_ERR_INVALID_ARG, "bad output mask");
@@ -513,18 +669,26 @@ int cell_plan(const chert_cache_desc* d, int64_t n_classes, const chert_cell_gri
   if (outs & CHERT_OUT_TAU_I) P->fields[P->nfs++] = 1;
   if ((int64_t)P->nfs * n_src > 65535) return fail(CHERT_ERR_UNSUPPORTED, "too many sources");
   P->n_prob = P->nfs * n_src;
-  if ((int64_t)P->n_prob * P->C >= 0x7fffffffLL || (int64_t)P->n_prob * P->n >= (1LL << 40))
+  if ((int64_t)P->n_prob * P->C >= 0x7fffffffLL / 4 || (int64_t)P->n_prob * P->n >= (1LL << 40))
     return fail(CHERT_ERR_UNSUPPORTED, "batch too large for one call");
   P->max_rounds = o->max_rounds > 0 ? o->max_rounds : 4096 + 64 * (g->ncx + g->ncz);
   const int s2 = P->side * P->side;
+  const size_t q3 = 2 * sizeof(double) + sizeof(int32_t);  // V, A, status
   size_t off = 0;
-  P->off_tab = off;  // L (double), then ox, oz, col (int32)
-  off += al256((size_t)s2 * (3 * sizeof(int32_t) + sizeof(double)));
+  P->off_tab = off;  // L (double), ox, oz, col, canon (int32), psi (double)
+  off += al256((size_t)s2 * (sizeof(double) + 4 * sizeof(int32_t)) +
+               (size_t)P->n_canon * sizeof(double) + 8);
   P->off_W = off;
-  off += al256((size_t)2 * n_classes * n_classes * s2 * sizeof(double));
+  if (!w.mspm) off += al256((size_t)2 * n_classes * n_classes * s2 * sizeof(double));
   P->off_best = off;
   if (P->slow) off += al256((size_t)n_classes * s2 * sizeof(int32_t));
-  P->off_ctl = off;  // count[2], err, alive, stats[3], wmin[2], minkey[3][P], bnd, cnt
+  P->off_kt = off;
+  if (w.mspm) off += al256((size_t)n_classes * P->n_canon * q3);
+  P->off_vt = off;
+  if (w.mspm) off += al256((size_t)4 * P->n_prob * P->C * P->n_canon * q3);
+  P->off_jobs = off;
+  if (w.mspm) off += al256((size_t)4 * P->n_prob * P->C * sizeof(int32_t));
+  P->off_ctl = off;  // count[2], err, alive, stats[4], wmin[2], minkey[3][P], bnd, cnt
   off += al256(256 + (size_t)3 * P->n_prob * sizeof(unsigned long long) +
                (size_t)6 * P->n_prob * sizeof(int32_t));
   P->off_src = off;
@@ -545,41 +709,28 @@ int cell_plan(const chert_cache_desc* d, int64_t n_classes, const chert_cell_gri
   return CHERT_OK;
 }
 
-}  // namespace
-}  // namespace chert
-
-using namespace chert;
-
-extern "C" size_t chert_trace_cells_workspace_bytes(const chert_cache_desc* d,
-                                                    int64_t n_classes,
-                                                    const chert_cell_grid* g, int32_t n_src,
-                                                    const chert_trace_opts* o) {
+size_t cell_workspace(const CellSrc& w, int64_t n_classes, const chert_cell_grid* g,
+                      int32_t n_src, const chert_trace_opts* o) {
   if (!g || n_src < 1) return 0;
   // sources are checked by the trace call; a lattice corner stands in here
   std::vector<int64_t> src((size_t)n_src, 0);
   CellPlan P;
-  if (cell_plan(d, n_classes, g, 0, src.data(), n_src, o, &P)) {
-    // the mode is checked by the trace call: retry with any cached mode
-    for (int m = 1; m < 3; ++m)
-      if (d && (d->mode_mask & (1u << m)) &&
-          cell_plan(d, n_classes, g, m, src.data(), n_src, o, &P) == CHERT_OK)
-        return P.total;
-    return 0;
-  }
-  return P.total;
+  for (int m = 0; m < 3; ++m)  // the mode is checked by the trace call
+    if (cell_plan(w, n_classes, g, m, src.data(), n_src, o, &P) == CHERT_OK) return P.total;
+  return 0;
 }
 
-extern "C" int chert_trace_cells(const chert_cache_desc* d, const void* cache_dev,
-                                 int64_t n_classes, const chert_cell_grid* g, int32_t mode,
-                                 const int64_t* src_nodes_host, int32_t n_src,
-                                 const chert_trace_opts* o, double* tau_r_dev, double* tau_i_dev,
-                                 double* tstar_dev, int32_t* pred_p_dev, int32_t* pred_a_dev,
-                                 void* workspace_dev, size_t workspace_bytes, void* stream) {
+int trace_cells_impl(const CellSrc& w, int64_t n_classes, const chert_cell_grid* g,
+                     int32_t mode, const int64_t* src_nodes_host, int32_t n_src,
+                     const chert_trace_opts* o, double* tau_r_dev, double* tau_i_dev,
+                     double* tstar_dev, int32_t* pred_p_dev, int32_t* pred_a_dev,
+                     void* workspace_dev, size_t workspace_bytes, void* stream) {
   CellPlan P;
-  int rc = cell_plan(d, n_classes, g, mode, src_nodes_host, n_src, o, &P);
+  int rc = cell_plan(w, n_classes, g, mode, src_nodes_host, n_src, o, &P);
   if (rc) return rc;
   const uint32_t outs = o->outputs;
-  if (!cache_dev) return fail(CHERT_ERR_INVALID_ARG, "null cache");
+  if (!w.mspm && !w.cache_dev) return fail(CHERT_ERR_INVALID_ARG, "null cache");
+  if (w.mspm && !w.classes_dev) return fail(CHERT_ERR_INVALID_ARG, "null classes");
   if ((outs & CHERT_OUT_TAU_R) && !tau_r_dev) return fail(CHERT_ERR_INVALID_ARG, "null tau_r");
   if ((outs & CHERT_OUT_TAU_I) && !tau_i_dev) return fail(CHERT_ERR_INVALID_ARG, "null tau_i");
   if ((outs & CHERT_OUT_TSTAR) && !tstar_dev) return fail(CHERT_ERR_INVALID_ARG, "null tstar");
@@ -593,9 +744,11 @@ extern "C" int chert_trace_cells(const chert_cache_desc* d, const void* cache_de
   const int K = (int)P.K;
 
   // segment offsets (dx, dz) in [-cn, cn]^2 (the centre is never a segment:
-  // a stand-in offset keeps the lookups finite), lengths (eq 27), columns
-  std::vector<int32_t> tab((size_t)s2 * 3);
-  std::vector<double> L((size_t)s2);
+  // a stand-in offset keeps the lookups finite), lengths (eq 27), columns;
+  // MSPM: canonical offsets (direction angle in [0, pi)) and their exact
+  // global ray angles
+  std::vector<int32_t> tab((size_t)s2 * 4);
+  std::vector<double> L((size_t)s2), psi((size_t)P.n_canon), Lc((size_t)P.n_canon);
   for (int dz = -cn; dz <= cn; ++dz)
     for (int dx = -cn; dx <= cn; ++dx) {
       const int q = (dz + cn) * side + (dx + cn);
@@ -605,15 +758,30 @@ extern "C" int chert_trace_cells(const chert_cache_desc* d, const void* cache_de
       const double ex = x * g->hx, ez = dz * g->hz;
       L[q] = sqrt(ex * ex + ez * ez);
       tab[2 * s2 + q] = 0;
+      tab[3 * s2 + q] = -1;
     }
-  if (!P.slow) {
+  {
+    int ci = 0;
+    for (int dz = -cn; dz <= cn; ++dz)
+      for (int dx = -cn; dx <= cn; ++dx) {
+        if (!(dx > 0 || (dx == 0 && dz > 0))) continue;
+        psi[ci] = atan2(dx * g->hx, dz * g->hz);
+        Lc[ci] = L[(dz + cn) * side + (dx + cn)];
+        tab[3 * s2 + (dz + cn) * side + (dx + cn)] = ci;
+        tab[3 * s2 + (-dz + cn) * side + (-dx + cn)] = ci;
+        ++ci;
+      }
+  }
+  if (!w.mspm && !P.slow) {
     std::vector<int32_t> bin((size_t)s2);
-    for (int q = 0; q < s2; ++q) bin[q] = star_bin_2d(tab[q], tab[s2 + q], g->hx, g->hz, d->n_dirs);
-    rc = star_columns(d, bin.data(), s2, tab.data() + 2 * s2);
+    for (int q = 0; q < s2; ++q)
+      bin[q] = star_bin_2d(tab[q], tab[s2 + q], g->hx, g->hz, w.d->n_dirs);
+    rc = star_columns(w.d, bin.data(), s2, tab.data() + 2 * s2);
     if (rc) return rc;
   }
   double* dL = (double*)(ws + P.off_tab);  // lengths first: 8-byte aligned
   int32_t* dtab = (int32_t*)(dL + s2);
+  double* dpsi = (double*)(dtab + 4 * s2);  // 24 s2 bytes in: 8-byte aligned
   int64_t* dsrc = (int64_t*)(ws + P.off_src);
   hipError_t e = hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(int32_t),
                                 hipMemcpyHostToDevice, s);
@@ -622,6 +790,8 @@ extern "C" int chert_trace_cells(const chert_cache_desc* d, const void* cache_de
   if (e == hipSuccess)
     e = hipMemcpyAsync(dsrc, src_nodes_host, (size_t)n_src * sizeof(int64_t),
                        hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && w.mspm)
+    e = hipMemcpyAsync(dpsi, psi.data(), psi.size() * sizeof(double), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // host buffers are locals
   if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
 
@@ -638,7 +808,7 @@ extern "C" int chert_trace_cells(const chert_cache_desc* d, const void* cache_de
   a.n = P.n;
   a.C = P.C;
   a.cls = g->class_id_dev;
-  a.W = (const double*)(ws + P.off_W);
+  a.W = w.mspm ? nullptr : (const double*)(ws + P.off_W);
   a.src = dsrc;
   a.count = (int32_t*)ctl;
   int32_t* err = (int32_t*)(ctl + 8);
@@ -666,6 +836,22 @@ extern "C" int chert_trace_cells(const chert_cache_desc* d, const void* cache_de
     if (a.pred[fi]) a.tree_mask |= 1 << fi;
   }
   a.tstar = (outs & CHERT_OUT_TSTAR) ? tstar_dev : nullptr;
+  a.mspm = w.mspm ? 1 : 0;
+  a.n_canon = P.n_canon;
+  a.canon = dtab + 3 * s2;
+  a.L = dL;
+  if (w.mspm) {
+    const int64_t kr = P.K * P.n_canon, vr = 4 * (int64_t)P.n_prob * P.C * P.n_canon;
+    uint8_t* kt = ws + P.off_kt;
+    a.kV = (const double*)kt;
+    a.kA = (const double*)(kt + kr * sizeof(double));
+    a.kS = (const int32_t*)(kt + 2 * kr * sizeof(double));
+    uint8_t* vt = ws + P.off_vt;
+    a.tV = (const double*)vt;
+    a.tA = (const double*)(vt + vr * sizeof(double));
+    a.tS = (const int32_t*)(vt + 2 * vr * sizeof(double));
+    a.job_class = (int32_t*)(ws + P.off_jobs);
+  }
 
   // class ids checked before any output is written
   CHERT_LAUNCH("k_cell_zero", k_cell_zero, dim3(1), dim3(1), 0, s, err);
@@ -678,26 +864,43 @@ extern "C" int chert_trace_cells(const chert_cache_desc* d, const void* cache_de
     if (herr) return fail(CHERT_ERR_INVALID_ARG, "class id out of range");
   }
 
-  // weights of both fields for every class pair and segment offset
-  chert_cache_layout lay;
-  chert_cache_layout_of(d, n_classes, &lay);
-  const uint8_t* cache = (const uint8_t*)cache_dev;
-  const int64_t ent = 3 * P.K * (int64_t)P.n_cols;
-  const int64_t mslice = (int64_t)mode * P.K * P.n_cols;
-  const double* fields = (const double*)(cache + lay.fields_offset);
-  const int32_t* Sm = (const int32_t*)(cache + lay.status_offset) + mslice;
-  int32_t* best = nullptr;
-  if (P.slow) {
-    best = (int32_t*)(ws + P.off_best);
-    enqueue_slow_lookup(best, K, P.n_cols, fields + CHERT_F_RX * ent + mslice,
-                        fields + CHERT_F_RZ * ent + mslice, Sm, s2, dtab, dtab + s2, g->hx,
-                        g->hz, s);
-  }
-  enqueue_pair_weights((double*)(ws + P.off_W), K, s2, fields + CHERT_F_V * ent + mslice,
-                       fields + CHERT_F_A * ent + mslice, Sm, P.n_cols, dL, dtab + 2 * s2, best,
-                       s);
   enqueue_wmin_init(wmin, s);
-  if (a.bucket > 0.0) enqueue_wmin((const double*)(ws + P.off_W), P.K * P.K * s2, wmin, s);
+  if (!w.mspm) {
+    // weights of both fields for every class pair and segment offset
+    chert_cache_layout lay;
+    chert_cache_layout_of(w.d, n_classes, &lay);
+    const uint8_t* cache = (const uint8_t*)w.cache_dev;
+    const int64_t ent = 3 * P.K * (int64_t)P.n_cols;
+    const int64_t mslice = (int64_t)mode * P.K * P.n_cols;
+    const double* fields = (const double*)(cache + lay.fields_offset);
+    const int32_t* Sm = (const int32_t*)(cache + lay.status_offset) + mslice;
+    int32_t* best = nullptr;
+    if (P.slow) {
+      best = (int32_t*)(ws + P.off_best);
+      enqueue_slow_lookup(best, K, P.n_cols, fields + CHERT_F_RX * ent + mslice,
+                          fields + CHERT_F_RZ * ent + mslice, Sm, s2, dtab, dtab + s2, g->hx,
+                          g->hz, s);
+    }
+    enqueue_pair_weights((double*)(ws + P.off_W), K, s2, fields + CHERT_F_V * ent + mslice,
+                         fields + CHERT_F_A * ent + mslice, Sm, P.n_cols, dL, dtab + 2 * s2,
+                         best, s);
+    if (a.bucket > 0.0) enqueue_wmin((const double*)(ws + P.off_W), P.K * P.K * s2, wmin, s);
+  } else {
+    // the class table (the tree phase and the ordering scale read it; the
+    // rounds solve their own corners afresh on every visit)
+    enqueue_mspm_solve(w.classes_dev, mode, w.kernel, w.n_sweep, nullptr, nullptr, 0, P.K, P.K,
+                       dpsi, P.n_canon, (double*)a.kV, (double*)a.kA, (int32_t*)a.kS, s);
+    if (a.bucket > 0.0) {
+      // canonical lengths ride in the visit table's first row until the
+      // rounds overwrite it
+      double* dLc = (double*)a.tV;
+      e = hipMemcpyAsync(dLc, Lc.data(), Lc.size() * sizeof(double), hipMemcpyHostToDevice, s);
+      if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+      CHERT_LAUNCH("k_mspm_wmin", k_mspm_wmin, dim3(64), dim3(256), 0, s, a, dLc, P.K);
+      e = hipStreamSynchronize(s);  // Lc is a local
+      if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+    }
+  }
 
   const unsigned gfill = (unsigned)((P.n + 255) / 256 > 256 ? 256 : (P.n + 255) / 256);
   CHERT_LAUNCH("k_cell_fill", k_cell_fill, dim3(gfill, (unsigned)P.n_prob), dim3(256), 0, s, a);
@@ -716,12 +919,20 @@ extern "C" int chert_trace_cells(const chert_cache_desc* d, const void* cache_de
   const size_t lds = (size_t)wpb * ns * ns * sizeof(double);
   const unsigned grelax =
       (unsigned)((items + wpb - 1) / wpb > 4096 ? 4096 : (items + wpb - 1) / wpb);
+  const unsigned gjobs = (unsigned)((4 * items + 255) / 256 > 1024 ? 1024 : (4 * items + 255) / 256);
+  const int64_t gsolve = 4 * items > 16384 ? 16384 : 4 * items;
   int rounds = -1;
   for (int r = 0; r < P.max_rounds && rounds < 0;) {
     const int group = r < 16 ? 16 : 32;
     const int nb = r + group > P.max_rounds ? P.max_rounds - r : group;
     for (int q = 0; q < nb; ++q) {
       CHERT_LAUNCH("k_cell_select", k_cell_select, dim3(gsel), dim3(256), 0, s, a, r + q);
+      if (w.mspm) {  // Algorithm 1: the visited cells' corners solved afresh
+        CHERT_LAUNCH("k_mspm_jobs", k_mspm_jobs, dim3(gjobs), dim3(256), 0, s, a, r + q);
+        enqueue_mspm_solve(w.classes_dev, mode, w.kernel, w.n_sweep, a.job_class,
+                           a.count + ((r + q) & 1), 4, 0, gsolve, dpsi, P.n_canon,
+                           (double*)a.tV, (double*)a.tA, (int32_t*)a.tS, s);
+      }
       CHERT_LAUNCH("k_cell_relax", k_cell_relax, dim3(grelax), dim3(64 * wpb), lds, s, a,
                    r + q);
     }
@@ -761,7 +972,7 @@ extern "C" int chert_trace_cells(const chert_cache_desc* d, const void* cache_de
     }
   }
   if (o->stats_host) {
-    unsigned long long st[3] = {0, 0, 0};
+    unsigned long long st[4] = {0, 0, 0, 0};
     e = hipMemcpyAsync(st, a.stats, sizeof(st), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
@@ -772,6 +983,62 @@ extern "C" int chert_trace_cells(const chert_cache_desc* d, const void* cache_de
     ts->tile_visits[0] = (int64_t)st[0];
     ts->edge_relaxations[0] = (int64_t)st[1];
     ts->levels_sum[0] = (int64_t)st[2];
+    // MSPM: (class, direction) solves of the rounds' corner tables
+    ts->edge_relaxations[1] = (int64_t)st[3] * P.n_canon;
   }
   return CHERT_OK;
+}
+
+}  // namespace
+}  // namespace chert
+
+using namespace chert;
+
+extern "C" size_t chert_trace_cells_workspace_bytes(const chert_cache_desc* d,
+                                                    int64_t n_classes,
+                                                    const chert_cell_grid* g, int32_t n_src,
+                                                    const chert_trace_opts* o) {
+  CellSrc w;
+  w.d = d;
+  return cell_workspace(w, n_classes, g, n_src, o);
+}
+
+extern "C" int chert_trace_cells(const chert_cache_desc* d, const void* cache_dev,
+                                 int64_t n_classes, const chert_cell_grid* g, int32_t mode,
+                                 const int64_t* src_nodes_host, int32_t n_src,
+                                 const chert_trace_opts* o, double* tau_r_dev, double* tau_i_dev,
+                                 double* tstar_dev, int32_t* pred_p_dev, int32_t* pred_a_dev,
+                                 void* workspace_dev, size_t workspace_bytes, void* stream) {
+  CellSrc w;
+  w.d = d;
+  w.cache_dev = cache_dev;
+  return trace_cells_impl(w, n_classes, g, mode, src_nodes_host, n_src, o, tau_r_dev, tau_i_dev,
+                          tstar_dev, pred_p_dev, pred_a_dev, workspace_dev, workspace_bytes,
+                          stream);
+}
+
+extern "C" size_t chert_trace_mspm_workspace_bytes(int64_t n_classes, const chert_cell_grid* g,
+                                                   int32_t n_src, const chert_trace_opts* o) {
+  CellSrc w;
+  w.mspm = true;
+  w.kernel = CHERT_KERNEL_MEV;
+  w.n_sweep = 8;
+  w.classes_dev = (const chert_class*)1;  // not dereferenced by the size query
+  return cell_workspace(w, n_classes, g, n_src, o);
+}
+
+extern "C" int chert_trace_mspm(const chert_class* classes_dev, int64_t n_classes,
+                                const chert_cell_grid* g, int32_t mode, int32_t kernel,
+                                int32_t n_sweep, const int64_t* src_nodes_host, int32_t n_src,
+                                const chert_trace_opts* o, double* tau_r_dev, double* tau_i_dev,
+                                double* tstar_dev, int32_t* pred_p_dev, int32_t* pred_a_dev,
+                                void* workspace_dev, size_t workspace_bytes, void* stream) {
+  CellSrc w;
+  w.mspm = true;
+  w.classes_dev = classes_dev;
+  w.kernel = kernel;
+  w.n_sweep = n_sweep;
+  return trace_cells_impl(w, n_classes, g, mode, src_nodes_host, n_src, o, tau_r_dev, tau_i_dev,
+                          tstar_dev, pred_p_dev, pred_a_dev, workspace_dev, workspace_bytes,
+                          stream);
 }

@@ -110,6 +110,16 @@ int enqueue_slow_lookup(int32_t* best, int K, int n_cols, const double* RX, cons
                         const int32_t* st, int n_off, const int32_t* ox_dev,
                         const int32_t* oz_dev, double hx, double hz, hipStream_t s);
 
+// MSPM's local tables (cache_build.hip): for each job q (class job_class[q],
+// or q itself when job_class is null; the job count is *n_jobs_dev times
+// n_jobs_mul when n_jobs_dev is given, else n_jobs_fixed) a fresh theta_R
+// sweep of n_sweep samples and one solve per target global ray angle
+// psi_dev[t]: V, A, status [q][t].  grid: workgroups (one job each at a time).
+int enqueue_mspm_solve(const chert_class* classes_dev, int mode, int kernel, int n_sweep,
+                       const int32_t* job_class, const int32_t* n_jobs_dev, int n_jobs_mul,
+                       int64_t n_jobs_fixed, int64_t grid, const double* psi_dev, int n_tgt,
+                       double* V, double* A, int32_t* st, hipStream_t s);
+
 // Kernel timing for chert_prof_*: returns a slot (or -1 when profiling is
 // off) after recording a start event on the stream; prof_end records the stop.
 int prof_begin(const char* name, hipStream_t s);
