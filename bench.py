@@ -332,6 +332,7 @@ def main():
     if not np.isfinite(tr):
         raise RuntimeError("bench produced an unreachable far corner")
 
+    opc = build_opcount(grids, wstats, build_ms * 1e-3, plain_s)
     kernels = {k: {"launches_per_step": v[0], "ms_per_step": v[1],
                    "avg_us": 1e3 * v[1] / max(v[0], 1)} for k, v in prof_all.items()}
     kernels[dom] = {"launches_per_step": prof[dom][0] / args.steps,
@@ -924,7 +925,7 @@ def run_shots(args):
             "shots_per_s_graph_trace_only": shots / graph_s if graph_s else None,
             "tau_R_rel_surrogate_vs_plain_max": worst, "tau_R_within_1e-4": worst <= 1e-4,
             "same_reachability": same_reach, "warm_status_equals_plain": same_status,
-            "warm_stats": wstats, "training": tinfo,
+            "warm_stats": wstats, "training": tinfo, "build_opcount": opc,
             "trace_stats_last_step": st,
             "raw_over_useful": {"tau": st["edge_relaxations"][0] / useful,
                                 "tree": st["edge_relaxations"][1] / useful},
@@ -938,6 +939,49 @@ def run_shots(args):
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline_shots(grids, solves, node_fields, shots, opts)
     print(json.dumps(res))
+
+
+def build_opcount(grids, wstats, warm_s, plain_s, n_sample=32):
+    """Algorithmic FP64 work of the per-node builds from an operation count
+    of the kernel source (paper_2609_26108_amd.opcount: physics.h and
+    solve.h compiled on the host with a counting scalar) on a sample of
+    solid nodes of the first grid, per mode: the theta_R sweep per class,
+    the plain solve per direction, and the surrogate start's polish per
+    direction (from a root offset by 1e-3 / 2e-4 rad, the surrogate's
+    typical miss).  Work per step = polished directions x polish cost +
+    plain-path jobs (fallbacks) x (sweep + directions x solve); rates over
+    the measured build times against the FP64 vector peak.  Transcendental
+    calls (sincos, expm1, atan2) are counted apart and not in the flops."""
+    import paper_2609_26108_amd as C
+    from paper_2609_26108_amd import opcount
+    g = grids[0]
+    rows = g["m"].param_rows()
+    solid = np.flatnonzero(rows[:, 1] > 0.0)
+    pick = solid[np.linspace(0, solid.size - 1, n_sample).astype(int)]
+    cls = np.stack([C.chert_class_from_thomsen(*r).as_array() for r in rows[pick]])
+    n_solve = len(g["sub"]) // 2
+    per = {}
+    for mode in (0, 1):
+        b = opcount.count(cls, n_dirs=2 * n_solve, n_sweep=g["desc"].n_sweep, mode=mode)["build"]
+        per[mode] = b
+    mean = {k: 0.5 * (per[0][k] + per[1][k]) for k in
+            ("sweep_flops_per_class", "solve_flops_per_direction", "warm_flops_per_direction",
+             "sweep_trans_per_class", "solve_trans_per_direction", "warm_trans_per_direction")}
+    jobs = sum(2 * gg["n"] for gg in grids)
+    plain_job = mean["sweep_flops_per_class"] + n_solve * mean["solve_flops_per_direction"]
+    warm_flops = (wstats["directions"] * mean["warm_flops_per_direction"] +
+                  wstats["fallback_jobs"] * plain_job)
+    plain_flops = jobs * plain_job
+    return {"per_mode": {str(m): per[m] for m in per}, "solved_directions_per_job": n_solve,
+            "energy_eval_flops": opcount.count(cls[:1], n_dirs=4, n_sweep=64)["MEV_qP"][
+                "energy_eval_flops"],
+            "warm_step_flops": warm_flops, "plain_build_flops": plain_flops,
+            "warm_tflops": warm_flops / warm_s / 1e12,
+            "warm_frac_fp64": warm_flops / warm_s / 1e12 / FP64_PEAK_TFLOPS,
+            "plain_tflops": plain_flops / plain_s / 1e12,
+            "plain_frac_fp64": plain_flops / plain_s / 1e12 / FP64_PEAK_TFLOPS,
+            "note": "counted add/sub/mul/div/sqrt of the source (an FMA = 2); transcendental "
+                    "calls apart; sample of solid nodes of the 401x201 grid"}
 
 
 def cpu_baseline_shots(grids, solves_total, node_fields_total, shots, opts):
