@@ -332,7 +332,6 @@ def main():
     if not np.isfinite(tr):
         raise RuntimeError("bench produced an unreachable far corner")
 
-    opc = build_opcount(grids, wstats, build_ms * 1e-3, plain_s)
     kernels = {k: {"launches_per_step": v[0], "ms_per_step": v[1],
                    "avg_us": 1e3 * v[1] / max(v[0], 1)} for k, v in prof_all.items()}
     kernels[dom] = {"launches_per_step": prof[dom][0] / args.steps,
@@ -874,6 +873,7 @@ def run_shots(args):
         worst = max(worst, float(rel.max().item()) if rel.numel() else 0.0)
     del warm_tau
 
+    opc = build_opcount(grids, wstats, build_ms * 1e-3, plain_s)
     kernels = {k: {"launches_per_step": v[0], "ms_per_step": v[1],
                    "avg_us": 1e3 * v[1] / max(v[0], 1)} for k, v in prof_all.items()}
     kernels[dom] = {"launches_per_step": prof[dom][0] / args.steps,
