@@ -949,8 +949,10 @@ def build_opcount(grids, wstats, warm_s, plain_s, n_sample=32):
     the plain solve per direction, and the surrogate start's polish per
     direction (from a root offset by 1e-3 / 2e-4 rad, the surrogate's
     typical miss).  Work per step = polished directions x polish cost +
-    plain-path jobs (fallbacks) x (sweep + directions x solve); rates over
-    the measured build times against the FP64 vector peak.  Transcendental
+    window samples x sweep-sample cost + plain-path jobs (fallbacks) x
+    (sweep + directions x solve); rates over
+    the measured build times against the FP64 vector peak; fold-window
+    samples count as sweep samples.  Transcendental
     calls (sincos, expm1, atan2) are counted apart and not in the flops."""
     import paper_2609_26108_amd as C
     from paper_2609_26108_amd import opcount
@@ -969,8 +971,10 @@ def build_opcount(grids, wstats, warm_s, plain_s, n_sample=32):
              "sweep_trans_per_class", "solve_trans_per_direction", "warm_trans_per_direction")}
     jobs = sum(2 * gg["n"] for gg in grids)
     plain_job = mean["sweep_flops_per_class"] + n_solve * mean["solve_flops_per_direction"]
+    # fold windows: each evaluated sample is one sweep sample's work
+    sample = mean["sweep_flops_per_class"] / g["desc"].n_sweep
     warm_flops = (wstats["directions"] * mean["warm_flops_per_direction"] +
-                  wstats["fallback_jobs"] * plain_job)
+                  wstats["window_samples"] * sample + wstats["fallback_jobs"] * plain_job)
     plain_flops = jobs * plain_job
     return {"per_mode": {str(m): per[m] for m in per}, "solved_directions_per_job": n_solve,
             "energy_eval_flops": opcount.count(cls[:1], n_dirs=4, n_sweep=64)["MEV_qP"][
