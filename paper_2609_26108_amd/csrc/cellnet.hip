@@ -138,6 +138,7 @@ struct CellArgs {
   const double* L;       // [side^2] segment lengths
   const double *tV, *tA;
   const int32_t* tS;     // visit tables
+  int w_lds;             // the class-pair table is staged in LDS by k_cell_relax
   const double *kV, *kA;
   const int32_t* kS;     // class table
   int32_t* job_class;    // [4 P C] class of each (visit, corner) solve job
@@ -148,7 +149,14 @@ struct CellArgs {
 // edge, at fraction t of the edge from q1, x = x1 + t (x2 - x1) for V and A.
 // Corner q: 0 = (0, 0), 1 = (cn, 0), 2 = (0, cn), 3 = (cn, cn); row[q] is
 // the table row of corner q.
-__device__ __forceinline__ int32_t mspm_node(int cn, const int64_t* row, int lx, int lz, int ci,
+struct Rows4 {
+  int64_t r0, r1, r2, r3;
+  __device__ __forceinline__ int64_t operator[](int q) const {
+    return q == 0 ? r0 : (q == 1 ? r1 : (q == 2 ? r2 : r3));  // selects, no memory
+  }
+};
+
+__device__ __forceinline__ int32_t mspm_node(int cn, const Rows4& row, int lx, int lz, int ci,
                                              const double* V, const double* A, const int32_t* S,
                                              double* v, double* at) {
   const bool ex = lx == 0 || lx == cn, ez = lz == 0 || lz == cn;
@@ -178,7 +186,7 @@ __device__ __forceinline__ int32_t mspm_node(int cn, const int64_t* row, int lx,
 
 // MSPM weight of the segment from local (ax, az) to (bx, bz) of one cell
 // (eqs 28-30 with the reconstructed end quantities); +inf if unusable
-__device__ __forceinline__ double mspm_w(const CellArgs& a, int f, const int64_t* row, int ax,
+__device__ __forceinline__ double mspm_w(const CellArgs& a, int f, const Rows4& row, int ax,
                                          int az, int bx, int bz, const double* V, const double* A,
                                          const int32_t* S) {
   const int cn = a.cn;
@@ -194,23 +202,22 @@ __device__ __forceinline__ double mspm_w(const CellArgs& a, int f, const int64_t
 
 // Weight of segment i -> j of cell c (field f): the class-pair table of a
 // cached network, or MSPM's reconstruction from the class table.
+template <bool MSPM>
 __device__ __forceinline__ double seg_weight(const CellArgs& a, int f, int c, int64_t i,
                                              int64_t j) {
   const int cn = a.cn;
   const int ix = (int)(i % a.NX), iz = (int)(i / a.NX), jx = (int)(j % a.NX), jz = (int)(j / a.NX);
-  if (!a.mspm) {
+  if constexpr (!MSPM) {
     const int64_t s2 = (int64_t)a.side * a.side;
     const int off = (jz - iz + cn) * a.side + (jx - ix + cn);
     return a.W[(int64_t)f * a.K * a.K * s2 + ((int64_t)a.cls[i] * a.K + a.cls[j]) * s2 + off];
+  } else {
+    const int x0 = (c % a.ncx) * cn, z0 = (c / a.ncx) * cn;
+    const int64_t n00 = (int64_t)x0 + (int64_t)a.NX * z0, dz = (int64_t)a.NX * cn;
+    const Rows4 row{(int64_t)a.cls[n00] * a.n_canon, (int64_t)a.cls[n00 + cn] * a.n_canon,
+                    (int64_t)a.cls[n00 + dz] * a.n_canon, (int64_t)a.cls[n00 + dz + cn] * a.n_canon};
+    return mspm_w(a, f, row, ix - x0, iz - z0, jx - x0, jz - z0, a.kV, a.kA, a.kS);
   }
-  const int x0 = (c % a.ncx) * cn, z0 = (c / a.ncx) * cn;
-  int64_t row[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t node = (int64_t)(x0 + (q & 1) * cn) + (int64_t)a.NX * (z0 + (q >> 1) * cn);
-    row[q] = (int64_t)a.cls[node] * a.n_canon;
-  }
-  return mspm_w(a, f, row, ix - x0, iz - z0, jx - x0, jz - z0, a.kV, a.kA, a.kS);
 }
 
 // a cell whose boundary holds both lattice nodes i and j
@@ -342,8 +349,10 @@ __global__ void k_cell_select(CellArgs a, int r) {
 // round r, step 3: relax the listed cells.  Each visit first stages the
 // weights of its ns x ns ordered pairs in LDS (one batch of independent
 // loads per lane), then runs the passes from LDS and lane broadcasts.
+template <bool MSPM>
 __global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) {
-  extern __shared__ double s_w[];  // [waves][ns][ns]
+  // dynamic LDS: [the class-pair table, when it fits][waves][ns][ns]
+  extern __shared__ double s_w[];
   __shared__ unsigned long long s_wake[kCellWaves][8];  // per neighbour cell
   const int lane = threadIdx.x & 63;
   const int wib = threadIdx.x >> 6;
@@ -353,7 +362,14 @@ __global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) 
   const int count = a.count[r & 1];
   const int cn = a.cn, ns = 4 * cn, side = a.side, K = a.K;
   const int64_t s2 = (int64_t)side * side;
-  double* wl = s_w + (size_t)wib * ns * ns;
+  const int64_t tab_n = a.w_lds ? 2LL * K * K * s2 : 0;
+  double* wl = s_w + tab_n + (size_t)wib * ns * ns;
+  // the whole class-pair table of both fields in LDS, once per workgroup
+  // with work (block-uniform), so a visit's weights are LDS reads
+  if (a.w_lds && blockIdx.x * wpb < count) {
+    for (int64_t q = threadIdx.x; q < tab_n; q += blockDim.x) s_w[q] = a.W[q];
+    __syncthreads();
+  }
   int lx = 0, lz = 0;
   if (lane < ns) slot_xy(lane, cn, lx, lz);
   unsigned long long visits = 0, pairs = 0, passes_all = 0;
@@ -363,7 +379,8 @@ __global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) 
     const int c = (int)(item - (int64_t)p * a.C);
     const int cx = c % a.ncx, cz = c / a.ncx;
     double* tau = tau_row(a, p);
-    const double* W = a.W ? a.W + (int64_t)a.field_of[p / a.n_src] * K * K * s2 : nullptr;
+    const double* W =
+        a.W ? (a.w_lds ? s_w : a.W) + (int64_t)a.field_of[p / a.n_src] * K * K * s2 : nullptr;
     const int gx = cx * cn + lx, gz = cz * cn + lz;
     const int64_t node = (int64_t)gx + (int64_t)a.NX * gz;
     int k = 0;
@@ -375,11 +392,10 @@ __global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) 
     // stage w(a -> lane) for every slot a (the diagonal is never read),
     // eight loads in flight per lane; slot a's class and position come from
     // lane a
-    if (a.mspm) {  // this visit's corner rows (solved for it this round)
+    if constexpr (MSPM) {  // this visit's corner rows (solved for it this round)
       const int f = a.field_of[p / a.n_src];
-      int64_t row[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) row[q] = ((int64_t)it * 4 + q) * a.n_canon;
+      const int64_t r0 = (int64_t)it * 4 * a.n_canon;
+      const Rows4 row{r0, r0 + a.n_canon, r0 + 2 * a.n_canon, r0 + 3 * a.n_canon};
       for (int sa = 0; sa < ns; ++sa) {
         const int ax = __builtin_amdgcn_readlane(lx, sa);
         const int az = __builtin_amdgcn_readlane(lz, sa);
@@ -430,10 +446,13 @@ __global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) 
     // once, with the smallest new traveltime among the nodes it shares
     if (lane < 8) s_wake[wib][lane] = kInfBits;
     wave_sync_lds();
+    // (the atomic's old value is not waited for: a node this visit lowered
+    // wakes its other cells even if another visit lowered it further, which
+    // costs at most a visit that changes nothing)
     if (lane < ns && t < t0) {
       const unsigned long long nb = dbits(t);
-      const unsigned long long old = atomicMin((unsigned long long*)&tau[node], nb);
-      if (nb < old) {
+      atomicMin((unsigned long long*)&tau[node], nb);
+      {
         const int ex = lx == 0 ? -1 : (lx == cn ? 1 : 0);
         const int ez = lz == 0 ? -1 : (lz == cn ? 1 : 0);
         // neighbour d = (dx + 1) + 3 (dz + 1), skipping the cell itself
@@ -476,6 +495,7 @@ __global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) 
 // when the previous launch ended): pred_j and t*_j = t*_pred + the
 // attenuation weight of that segment (the parent's value final one level
 // earlier).  Level bounds rotate through three slots per problem.
+template <bool MSPM>
 __global__ void __launch_bounds__(256) k_cell_level(CellArgs a, int L) {
   const int p = blockIdx.y;
   const int fi = p / a.n_src, s = p - fi * a.n_src;
@@ -517,10 +537,11 @@ __global__ void __launch_bounds__(256) k_cell_level(CellArgs a, int L) {
     const double tj = tau[j], tv = tau[v];
     const int hv = hop[v];
     if (L > 0 && hv == L - 1) {  // v -> j tight?
-      if (tv + seg_weight(a, f, cs[q], v, j) == tj) atomicMin(&bid[j], (int)v);
+      if (tv + seg_weight<MSPM>(a, f, cs[q], v, j) == tj) atomicMin(&bid[j], (int)v);
     }
     if (hv == -1 && tv < INFINITY) {  // j -> v tight?
-      if (tj + seg_weight(a, f, cs[q], j, v) == tv && atomicCAS(&hop[v], -1, L + 1) == -1) {
+      if (tj + seg_weight<MSPM>(a, f, cs[q], j, v) == tv &&
+          atomicCAS(&hop[v], -1, L + 1) == -1) {
         bfs[end + atomicAdd(cnt, 1)] = (int32_t)v;
         ++added;
       }
@@ -535,7 +556,7 @@ __global__ void __launch_bounds__(256) k_cell_level(CellArgs a, int L) {
       // in bounds
       if (b == 0x7fffffff) continue;
       if (pred) pred[j] = b;
-      if (ts) ts[j] = ts[b] + seg_weight(a, 1, common_cell(a, b, j), b, j);
+      if (ts) ts[j] = ts[b] + seg_weight<MSPM>(a, 1, MSPM ? common_cell(a, b, j) : 0, b, j);
     }
   }
   for (int o = 32; o > 0; o >>= 1) added += __shfl_xor(added, o);
@@ -916,6 +937,10 @@ int trace_cells_impl(const CellSrc& w, int64_t n_classes, const chert_cell_grid*
   int wpb = (int)(65536 / ((size_t)ns * ns * sizeof(double)));
   if (wpb > kCellWaves) wpb = kCellWaves;
   if (wpb < 1) wpb = 1;
+  // (staging the whole class-pair table in LDS per workgroup measured
+  // slower: fewer resident workgroups, and the table load costs more than
+  // the weight loads it saves)
+  a.w_lds = 0;
   const size_t lds = (size_t)wpb * ns * ns * sizeof(double);
   const unsigned grelax =
       (unsigned)((items + wpb - 1) / wpb > 4096 ? 4096 : (items + wpb - 1) / wpb);
@@ -933,8 +958,12 @@ int trace_cells_impl(const CellSrc& w, int64_t n_classes, const chert_cell_grid*
                            a.count + ((r + q) & 1), 4, 0, gsolve, dpsi, P.n_canon,
                            (double*)a.tV, (double*)a.tA, (int32_t*)a.tS, s);
       }
-      CHERT_LAUNCH("k_cell_relax", k_cell_relax, dim3(grelax), dim3(64 * wpb), lds, s, a,
-                   r + q);
+      if (w.mspm)
+        CHERT_LAUNCH("k_cell_relax", k_cell_relax<true>, dim3(grelax), dim3(64 * wpb), lds, s,
+                     a, r + q);
+      else
+        CHERT_LAUNCH("k_cell_relax", k_cell_relax<false>, dim3(grelax), dim3(64 * wpb), lds, s,
+                     a, r + q);
     }
     r += nb;
     int32_t cnt = 0;
@@ -956,8 +985,12 @@ int trace_cells_impl(const CellSrc& w, int64_t n_classes, const chert_cell_grid*
     for (int Lv = 0;;) {
       CHERT_LAUNCH("k_cell_zero", k_cell_zero, dim3(1), dim3(1), 0, s, a.alive);
       for (int q = 0; q < 8; ++q, ++Lv)
-        CHERT_LAUNCH("k_cell_level", k_cell_level, dim3(gx, (unsigned)P.n_prob), dim3(256), 0,
-                     s, a, Lv);
+        if (w.mspm)
+          CHERT_LAUNCH("k_cell_level", k_cell_level<true>, dim3(gx, (unsigned)P.n_prob),
+                       dim3(256), 0, s, a, Lv);
+        else
+          CHERT_LAUNCH("k_cell_level", k_cell_level<false>, dim3(gx, (unsigned)P.n_prob),
+                       dim3(256), 0, s, a, Lv);
       int32_t alive = 0;
       e = hipMemcpyAsync(&alive, a.alive, sizeof(int32_t), hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
