@@ -75,6 +75,8 @@ def lib():
                                          P, P, P, P, P]
         L.orc_trace_mspm_2d.argtypes = [l, l, i, d, d, P, P, l, i, i, i, l, i,
                                         P, P, P, P, P, P]
+        L.orc_trace_blocks_3d.argtypes = [l, l, l, i, d, d, d, P, l, i, P, P, P, l, i,
+                                          P, P, P, P, P]
         L.orc_slow_lookup.argtypes = [l, i, P, P, P, i, P, P, d, d, P]
         L.orc_trace_2d_slow.argtypes = [l, l, d, d, P, l, i, i, P, P, P, P, P, l, P, P, P, P, P]
         _lib = L
@@ -377,6 +379,42 @@ def trace_cells_2d(ncx, ncz, cn, hx, hz, class_id, f_mode, st_mode, src, samplin
                                   _p(out["predA"]), _p(out["tstar"]))
     if rc:
         raise ValueError(f"orc_trace_cells_2d failed rc={rc}")
+    return out
+
+
+def block_lattice(ncx, ncy, ncz, cn):
+    """(NX, NY, NZ, mask[NZ, NY, NX]): lattice of a 3D block network and which
+    lattice points are nodes (on a block face)."""
+    NX, NY, NZ = ncx * cn + 1, ncy * cn + 1, ncz * cn + 1
+    ix = np.arange(NX)[None, None, :]
+    iy = np.arange(NY)[None, :, None]
+    iz = np.arange(NZ)[:, None, None]
+    return NX, NY, NZ, ((ix % cn == 0) | (iy % cn == 0) | (iz % cn == 0))
+
+
+def trace_blocks_3d(ncx, ncy, ncz, cn, hx, hy, hz, class_id, V, A, status, src, N=N_FIB,
+                    block=False):
+    """3D block network (nodes on block faces, all pairs within a block):
+    V, A, status = one mode of a 3D cache ([K][N]); each segment reads the
+    Fibonacci direction closest to it.  Returns lattice-sized tauR, tauI,
+    predP, predA, tstar (node ix + NX (iy + NY iz))."""
+    NX, NY, NZ, _ = block_lattice(ncx, ncy, ncz, cn)
+    n = NX * NY * NZ
+    cid = np.ascontiguousarray(class_id, dtype=np.int32).reshape(-1)
+    assert cid.size == n
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    st = np.ascontiguousarray(status, dtype=np.int32)
+    K = st.shape[0]
+    assert V.shape == (K, N) and A.shape == (K, N) and st.shape == (K, N)
+    out = {k: np.zeros(n) for k in ("tauR", "tauI", "tstar")}
+    out.update({k: np.zeros(n, np.int32) for k in ("predP", "predA")})
+    rc = lib().orc_trace_blocks_3d(ncx, ncy, ncz, cn, hx, hy, hz, _p(cid), K, N, _p(V), _p(A),
+                                   _p(st), int(src), int(bool(block)), _p(out["tauR"]),
+                                   _p(out["tauI"]), _p(out["predP"]), _p(out["predA"]),
+                                   _p(out["tstar"]))
+    if rc:
+        raise ValueError(f"orc_trace_blocks_3d failed rc={rc}")
     return out
 
 

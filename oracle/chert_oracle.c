@@ -1416,6 +1416,8 @@ out:
 typedef struct {
   long ncx, ncz, NX, NZ;
   int cn, side;          /* side = 2 cn + 1: offsets (dx, dz) in [-cn, cn]^2 */
+  int dim;               /* 2, or 3 for blocks (O-20) */
+  long ncy, NY;          /* 3D: blocks and lattice points along y (2D: 1, 1) */
   const int32_t *cls;    /* lattice -> class */
   long K;
   int n_cols;
@@ -1441,13 +1443,28 @@ static int cell_off(const cellnet_t *g, long dx, long dz) {
   return (int)((dz + g->cn) * g->side + (dx + g->cn));
 }
 
+/* lattice node index ix + NX (iy + NY iz) and back (2D: iy = 0, NY = 1) */
+static long cell_n_nodes(const cellnet_t *g) { return g->NX * g->NY * g->NZ; }
+static void cell_xyz(const cellnet_t *g, long u, long *x, long *y, long *z) {
+  *x = u % g->NX;
+  *y = (u / g->NX) % g->NY;
+  *z = u / (g->NX * g->NY);
+}
+/* offset index: 2D (dz, dx), 3D (dz, dy, dx), each in [-cn, cn] */
+static int cell_off3(const cellnet_t *g, long dx, long dy, long dz) {
+  if (g->dim == 2) return cell_off(g, dx, dz);
+  return (int)(((dz + g->cn) * g->side + (dy + g->cn)) * g->side + (dx + g->cn));
+}
+
 static double mspm_weight(cellnet_t *g, int field, long c, long i, long j);
 
 /* Weight of segment i -> j of cell c (the cell matters only to MSPM). */
 static double cell_weight(cellnet_t *g, int field, long c, long i, long j) {
   if (g->mspm) return mspm_weight(g, field, c, i, j);
-  long dx = (j % g->NX) - (i % g->NX), dz = (j / g->NX) - (i / g->NX);
-  int o = cell_off(g, dx, dz);
+  long xi, yi, zi, xj, yj, zj;
+  cell_xyz(g, i, &xi, &yi, &zi);
+  cell_xyz(g, j, &xj, &yj, &zj);
+  int o = cell_off3(g, xj - xi, yj - yi, zj - zi);
   long ki = g->cls[i], kj = g->cls[j];
   int ci, cj;
   if (g->best) {
@@ -1464,38 +1481,49 @@ static double cell_weight(cellnet_t *g, int field, long c, long i, long j) {
   return g->L[o] * (0.5 * (g->A[ki * g->n_cols + ci] + g->A[kj * g->n_cols + cj]));
 }
 
-/* The cells whose boundary holds lattice node u: up to two columns and two
- * rows of cells.  Writes cell indices cx + ncx cz into c[], returns count. */
-static int cells_of(const cellnet_t *g, long u, long *c) {
-  long ix = u % g->NX, iz = u / g->NX;
-  long xs[2], zs[2];
-  int nxs = 0, nzs = 0;
-  if (ix % g->cn == 0) {
-    if (ix / g->cn - 1 >= 0) xs[nxs++] = ix / g->cn - 1;
-    if (ix / g->cn < g->ncx) xs[nxs++] = ix / g->cn;
-  } else {
-    xs[nxs++] = ix / g->cn;
-  }
-  if (iz % g->cn == 0) {
-    if (iz / g->cn - 1 >= 0) zs[nzs++] = iz / g->cn - 1;
-    if (iz / g->cn < g->ncz) zs[nzs++] = iz / g->cn;
-  } else {
-    zs[nzs++] = iz / g->cn;
-  }
+/* the cell indices along one axis whose closed range holds coordinate q */
+static int cells_along(long q, int cn, long ncells, long *out) {
   int n = 0;
-  for (int a = 0; a < nxs; ++a)
-    for (int b = 0; b < nzs; ++b) c[n++] = xs[a] + g->ncx * zs[b];
+  if (q % cn == 0) {
+    if (q / cn - 1 >= 0) out[n++] = q / cn - 1;
+    if (q / cn < ncells) out[n++] = q / cn;
+  } else {
+    out[n++] = q / cn;
+  }
   return n;
 }
 
-/* The 4 cn boundary nodes of cell c (each once), in any order. */
+/* The cells (blocks) whose boundary holds lattice node u: up to two per
+ * axis.  Writes cell indices cx + ncx (cy + ncy cz) into c[] (at most 4 in
+ * 2D, 8 in 3D), returns the count. */
+static int cells_of(const cellnet_t *g, long u, long *c) {
+  long ix, iy, iz;
+  cell_xyz(g, u, &ix, &iy, &iz);
+  long xs[2], ys[2] = {0, 0}, zs[2];
+  int nxs = cells_along(ix, g->cn, g->ncx, xs);
+  int nys = g->dim == 3 ? cells_along(iy, g->cn, g->ncy, ys) : 1;
+  int nzs = cells_along(iz, g->cn, g->ncz, zs);
+  int n = 0;
+  for (int a = 0; a < nxs; ++a)
+    for (int d = 0; d < nys; ++d)
+      for (int b = 0; b < nzs; ++b) c[n++] = xs[a] + g->ncx * (ys[d] + g->ncy * zs[b]);
+  return n;
+}
+
+/* The boundary nodes of cell c (each once), in any order: 4 cn in 2D, the
+ * (cn + 1)^3 - (cn - 1)^3 face points of a block in 3D. */
 static int cell_nodes(const cellnet_t *g, long c, long *v) {
-  long x0 = (c % g->ncx) * g->cn, z0 = (c / g->ncx) * g->cn;
+  long x0 = (c % g->ncx) * g->cn, y0 = ((c / g->ncx) % g->ncy) * g->cn,
+       z0 = (c / (g->ncx * g->ncy)) * g->cn;
+  long ny = g->dim == 3 ? g->cn : 0;
   int n = 0;
   for (long dz = 0; dz <= g->cn; ++dz)
-    for (long dx = 0; dx <= g->cn; ++dx)
-      if (dx == 0 || dz == 0 || dx == g->cn || dz == g->cn)
-        v[n++] = (x0 + dx) + g->NX * (z0 + dz);
+    for (long dy = 0; dy <= ny; ++dy)
+      for (long dx = 0; dx <= g->cn; ++dx) {
+        int on = dx == 0 || dz == 0 || dx == g->cn || dz == g->cn;
+        if (g->dim == 3) on = on || dy == 0 || dy == g->cn;
+        if (on) v[n++] = (x0 + dx) + g->NX * ((y0 + dy) + g->NY * (z0 + dz));
+      }
   return n;
 }
 
@@ -1504,7 +1532,7 @@ static int cell_nodes(const cellnet_t *g, long c, long *v) {
  * listed twice; the two copies are the same segment and carry the same
  * weight). */
 static int cell_neighbours(const cellnet_t *g, long u, long *nb, long *nbc) {
-  long cs[4], v[64 * 4];
+  long cs[8], v[64 * 4];
   int nc = cells_of(g, u, cs), n = 0;
   for (int a = 0; a < nc; ++a) {
     int m = cell_nodes(g, cs[a], v);
@@ -1519,18 +1547,22 @@ static int cell_neighbours(const cellnet_t *g, long u, long *nb, long *nbc) {
 
 /* A cell whose boundary holds both nodes i and j. */
 static long common_cell(const cellnet_t *g, long i, long j) {
-  long cs[4];
+  long cs[8];
   int nc = cells_of(g, j, cs);
-  long ix = i % g->NX, iz = i / g->NX;
+  long ix, iy, iz;
+  cell_xyz(g, i, &ix, &iy, &iz);
   for (int a = 0; a < nc; ++a) {
-    long x0 = (cs[a] % g->ncx) * g->cn, z0 = (cs[a] / g->ncx) * g->cn;
-    if (ix >= x0 && ix <= x0 + g->cn && iz >= z0 && iz <= z0 + g->cn) return cs[a];
+    long x0 = (cs[a] % g->ncx) * g->cn, y0 = ((cs[a] / g->ncx) % g->ncy) * g->cn,
+         z0 = (cs[a] / (g->ncx * g->ncy)) * g->cn;
+    if (ix >= x0 && ix <= x0 + g->cn && iz >= z0 && iz <= z0 + g->cn &&
+        (g->dim == 2 || (iy >= y0 && iy <= y0 + g->cn)))
+      return cs[a];
   }
   return -1;
 }
 
 static int cell_dijkstra(cellnet_t *g, int field, long src, double *tau) {
-  long n = g->NX * g->NZ;
+  long n = cell_n_nodes(g);
   for (long i = 0; i < n; ++i) tau[i] = INFINITY;
   char *done = (char *)calloc((size_t)n, 1);
   long *nb = (long *)malloc(sizeof(long) * 16 * 64);
@@ -1574,11 +1606,11 @@ out:
  * network's shortest-path traveltimes (the same fixed point as node
  * Dijkstra) whatever the order. */
 static int cell_block_march(cellnet_t *g, int field, long src, double *tau) {
-  long n = g->NX * g->NZ, nc = g->ncx * g->ncz;
+  long n = cell_n_nodes(g), nc = g->ncx * g->ncy * g->ncz;
   for (long i = 0; i < n; ++i) tau[i] = INFINITY;
   double *key = (double *)malloc(sizeof(double) * (size_t)nc);
   long *v = (long *)malloc(sizeof(long) * 64 * 4);
-  long cs[4];
+  long cs[8];
   heap_t h = {0, 0, 0};
   int rc = 0;
   if (!key || !v) { rc = 1; goto out; }
@@ -1643,7 +1675,7 @@ out:
  * that tree from the source outwards. */
 static int cell_predecessors(cellnet_t *g, int field, long src, const double *tau,
                              int32_t *pred, double *tstar) {
-  long n = g->NX * g->NZ;
+  long n = cell_n_nodes(g);
   int32_t *hop = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
   long *order = (long *)malloc(sizeof(long) * (size_t)n);
   long *nb = (long *)malloc(sizeof(long) * 16 * 64);
@@ -1699,7 +1731,7 @@ static int cell_predecessors(cellnet_t *g, int field, long src, const double *ta
 static int cell_fields(cellnet_t *g, long src, int block, double *t, int32_t *p,
                        double *tauR, double *tauI, int32_t *predP, int32_t *predA,
                        double *tstar) {
-  long n = g->NX * g->NZ;
+  long n = cell_n_nodes(g);
   for (int field = 0; field < 2; ++field) {
     double *out_t = field ? tauI : tauR;
     int32_t *out_p = field ? predA : predP;
@@ -1728,8 +1760,8 @@ int orc_trace_cells_2d(long ncx, long ncz, int cn, double hx, double hz,
                        int32_t *predP, int32_t *predA, double *tstar) {
   if (ncx < 1 || ncz < 1 || cn < 1 || cn > 16 || !class_id) return 1;
   cellnet_t g = {.ncx = ncx, .ncz = ncz, .NX = ncx * cn + 1, .NZ = ncz * cn + 1, .cn = cn,
-                 .side = 2 * cn + 1, .cls = class_id, .K = K, .n_cols = n_cols, .V = V,
-                 .A = A, .st = st};
+                 .side = 2 * cn + 1, .dim = 2, .ncy = 1, .NY = 1, .cls = class_id, .K = K,
+                 .n_cols = n_cols, .V = V, .A = A, .st = st};
   long n = g.NX * g.NZ;
   if (src < 0 || src >= n || !cell_is_node(&g, src % g.NX, src / g.NX)) return 1;
   int n_o = g.side * g.side;
@@ -1874,7 +1906,8 @@ int orc_trace_mspm_2d(long ncx, long ncz, int cn, double hx, double hz,
                       long *n_solves) {
   if (ncx < 1 || ncz < 1 || cn < 1 || cn > 16 || !class_id || n_sweep < 8) return 1;
   cellnet_t g = {.ncx = ncx, .ncz = ncz, .NX = ncx * cn + 1, .NZ = ncz * cn + 1, .cn = cn,
-                 .side = 2 * cn + 1, .cls = class_id, .K = K, .mspm = 1, .classes = classes,
+                 .side = 2 * cn + 1, .dim = 2, .ncy = 1, .NY = 1, .cls = class_id, .K = K,
+                 .mspm = 1, .classes = classes,
                  .mode = mode, .reading = reading, .n_sweep = n_sweep, .hx = hx, .hz = hz};
   long n = g.NX * g.NZ;
   if (src < 0 || src >= n || !cell_is_node(&g, src % g.NX, src / g.NX)) return 1;
@@ -1901,5 +1934,69 @@ int orc_trace_mspm_2d(long ncx, long ncz, int cn, double hx, double hz,
   }
 out:
   free(t); free(p); free(g.L); free(g.mV); free(g.mA); free(g.mst);
+  return rc;
+}
+
+
+/* ------------------------------------------------------------------------ */
+/* O-20  the cell network in 3D: blocks (section on 3D extension, eq 35)    */
+/* ------------------------------------------------------------------------ */
+
+/* ncx x ncy x ncz blocks of cn intervals per side (hx, hy, hz).  Nodes are
+ * the lattice points on a block face (any coordinate a multiple of cn),
+ * indexed ix + NX (iy + NY iz); two nodes are joined when both lie on the
+ * boundary of one block.  Weights follow eqs 28-30 with both ends reading the
+ * Fibonacci direction closest to the segment (largest dot product with its
+ * unit vector; the lowest index among equals, the 3D forward-star rule).
+ * V, A, st: [K][N] slices of one mode of a 3D cache; outputs as for
+ * orc_trace_cells_2d, lattice-sized, interior points +inf / -1. */
+int orc_trace_blocks_3d(long ncx, long ncy, long ncz, int cn, double hx, double hy,
+                        double hz, const int32_t *class_id, long K, int N, const double *V,
+                        const double *A, const int32_t *st, long src, int block, double *tauR,
+                        double *tauI, int32_t *predP, int32_t *predA, double *tstar) {
+  if (ncx < 1 || ncy < 1 || ncz < 1 || cn < 1 || cn > 4 || !class_id || N < 2) return 1;
+  cellnet_t g = {.ncx = ncx, .ncz = ncz, .NX = ncx * cn + 1, .NZ = ncz * cn + 1, .cn = cn,
+                 .side = 2 * cn + 1, .dim = 3, .ncy = ncy, .NY = ncy * cn + 1,
+                 .cls = class_id, .K = K, .n_cols = N, .V = V, .A = A, .st = st};
+  long n = cell_n_nodes(&g);
+  if (src < 0 || src >= n) return 1;
+  {
+    long x, y, z;
+    cell_xyz(&g, src, &x, &y, &z);
+    if (!(x % cn == 0 || y % cn == 0 || z % cn == 0)) return 1;
+  }
+  int n_o = g.side * g.side * g.side;
+  double *t = (double *)malloc(sizeof(double) * (size_t)n);
+  int32_t *p = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  double *f = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+  g.L = (double *)malloc(sizeof(double) * n_o);
+  g.colR = (int32_t *)malloc(sizeof(int32_t) * n_o);
+  int rc = 0;
+  if (!t || !p || !f || !g.L || !g.colR) { rc = 2; goto out; }
+  orc_fibonacci(N, f);
+  for (int z = -cn; z <= cn; ++z)
+    for (int y = -cn; y <= cn; ++y)
+      for (int x = -cn; x <= cn; ++x) {
+        int o = cell_off3(&g, x, y, z);
+        if (x == 0 && y == 0 && z == 0) { /* the centre is never a segment */
+          g.L[o] = 0.0;
+          g.colR[o] = 0;
+          continue;
+        }
+        double dx = x * hx, dy = y * hy, dz = z * hz;
+        double len = sqrt(dx * dx + dz * dz + dy * dy);
+        double u0 = dx / len, u1 = dy / len, u2 = dz / len;
+        int best = 0;
+        double bd = -2.0;
+        for (int i = 0; i < N; ++i) {
+          double d = f[3 * i] * u0 + f[3 * i + 1] * u1 + f[3 * i + 2] * u2;
+          if (d > bd) { bd = d; best = i; }
+        }
+        g.L[o] = len;
+        g.colR[o] = best;
+      }
+  rc = cell_fields(&g, src, block, t, p, tauR, tauI, predP, predA, tstar);
+out:
+  free(t); free(p); free(f); free(g.L); free(g.colR);
   return rc;
 }
