@@ -554,6 +554,48 @@ int chert_trace_mspm(const chert_class *classes_dev, int64_t n_classes,
                      int32_t *pred_p_dev, int32_t *pred_a_dev, void *workspace_dev,
                      size_t workspace_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * The block network: the cell network in 3D (the discretisation section
+ * names cells in 2D and blocks in 3D; eqs 27-31 with the 3D cache of
+ * eq 35).  The medium is cut into ncx x ncy x ncz boxes whose edges hold
+ * block_n intervals of hx, hy or hz.  The nodes are the points of the
+ * NX x NY x NZ lattice (N? = nc? block_n + 1) that lie on a block face (any
+ * coordinate a multiple of block_n), indexed ix + NX (iy + NY iz); every
+ * pair of face points of one block is joined by the straight segment
+ * between them, whose weight is eqs 28-30 with the classes of its two end
+ * nodes, both read at the cache's Fibonacci direction closest to the
+ * segment (largest dot product with its unit vector, the lowest index among
+ * equals: the 3D forward star's rule).  Traveltimes, predecessors and t*
+ * follow the same rules as chert_trace_cells.
+ * ---------------------------------------------------------------------- */
+typedef struct chert_block_grid {
+  int32_t ncx, ncy, ncz; /* blocks along x, y and z (>= 1)                 */
+  int32_t block_n;       /* intervals per block edge, 1..3 (at most 56
+                            face nodes per block, one lane each)           */
+  double hx, hy, hz;     /* lattice spacing along x, y and z [m]           */
+  const int32_t *class_id_dev; /* [NZ][NY][NX] class of every lattice
+                            point (read at nodes only; required)            */
+} chert_block_grid;
+
+/* Workspace of chert_trace_blocks (0 on invalid arguments). */
+size_t chert_trace_blocks_workspace_bytes(const chert_cache_desc *d, int64_t n_classes,
+                                          const chert_block_grid *g, int32_t n_src,
+                                          const chert_trace_opts *o);
+
+/* Trace n_src sources (lattice indices of nodes) of one mode on the block
+ * network of g with a 3D class cache (d->dim == 3, n_dirs Fibonacci
+ * directions).  Outputs are device arrays [n_src][NX NY NZ]; lattice points
+ * inside blocks get +inf (tau, t*) and -1 (pred).  Options, statistics
+ * (cell visits count block visits) and errors as chert_trace_cells;
+ * INVALID_ARG on a 2D cache or a source inside a block.  Synchronous with
+ * respect to `stream`. */
+int chert_trace_blocks(const chert_cache_desc *d, const void *cache_dev, int64_t n_classes,
+                       const chert_block_grid *g, int32_t mode, const int64_t *src_nodes_host,
+                       int32_t n_src, const chert_trace_opts *o, double *tau_r_dev,
+                       double *tau_i_dev, double *tstar_dev, int32_t *pred_p_dev,
+                       int32_t *pred_a_dev, void *workspace_dev, size_t workspace_bytes,
+                       void *stream);
+
 /* Raypath (eqs 25, 33-34): follow pred from rcv back to src and write the
  * node sequence src ... rcv into path_out.  Host, synchronous.
  * *path_len receives the length (also on CAPACITY, so the caller can retry).

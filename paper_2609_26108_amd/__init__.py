@@ -47,6 +47,7 @@ EXPORTS = (
     "chert_star_3d", "chert_build_cache_noalloc", "chert_build_cache_noalloc_max_bytes",
     "chert_trace_cells_workspace_bytes", "chert_trace_cells",
     "chert_trace_mspm_workspace_bytes", "chert_trace_mspm",
+    "chert_trace_blocks_workspace_bytes", "chert_trace_blocks",
 )
 WARM_NSTATS = 10
 # parameter blocks of the surrogate, in their order in the parameter vector
@@ -112,6 +113,12 @@ class CellGrid(ctypes.Structure):
     _fields_ = [("ncx", ctypes.c_int32), ("ncz", ctypes.c_int32), ("cell_n", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("hx", ctypes.c_double), ("hz", ctypes.c_double),
                 ("class_id_dev", ctypes.c_void_p)]
+
+
+class BlockGrid(ctypes.Structure):
+    _fields_ = [("ncx", ctypes.c_int32), ("ncy", ctypes.c_int32), ("ncz", ctypes.c_int32),
+                ("block_n", ctypes.c_int32), ("hx", ctypes.c_double), ("hy", ctypes.c_double),
+                ("hz", ctypes.c_double), ("class_id_dev", ctypes.c_void_p)]
 
 
 class TraceJob(ctypes.Structure):
@@ -217,6 +224,9 @@ def lib():
         L.chert_trace_cells_workspace_bytes.argtypes = [P, i64, P, i32, P]
         L.chert_trace_cells_workspace_bytes.restype = sz
         L.chert_trace_cells.argtypes = [P, P, i64, P, i32, P, i32, P, P, P, P, P, P, P, sz, P]
+        L.chert_trace_blocks_workspace_bytes.argtypes = [P, i64, P, i32, P]
+        L.chert_trace_blocks_workspace_bytes.restype = sz
+        L.chert_trace_blocks.argtypes = [P, P, i64, P, i32, P, i32, P, P, P, P, P, P, P, sz, P]
         L.chert_trace_mspm_workspace_bytes.argtypes = [i64, P, i32, P]
         L.chert_trace_mspm_workspace_bytes.restype = sz
         L.chert_trace_mspm.argtypes = [P, i64, P, i32, i32, i32, P, i32, P, P, P, P, P, P, P,
@@ -449,6 +459,31 @@ def chert_trace_cells(desc, cache_dev, n_classes, grid, mode, src_nodes: Sequenc
     src = np.ascontiguousarray(np.asarray(src_nodes, dtype=np.int64).reshape(-1))
     ws = workspace_dev.numel() * workspace_dev.element_size() if workspace_dev is not None else 0
     _check(lib().chert_trace_cells(
+        ctypes.byref(desc), _ptr(cache_dev), n_classes, ctypes.byref(grid), mode,
+        src.ctypes.data, int(src.size), ctypes.byref(opts), _ptr(tau_r), _ptr(tau_i),
+        _ptr(tstar), _ptr(pred_p), _ptr(pred_a), _ptr(workspace_dev), ws, _stream(stream)))
+
+
+def make_block_grid(ncx, ncy, ncz, block_n, hx, hy, hz, class_id_dev):
+    """Block network: ncx x ncy x ncz blocks of block_n intervals per edge;
+    the class map covers the (ncz n + 1) x (ncy n + 1) x (ncx n + 1) lattice."""
+    g = BlockGrid(ncx, ncy, ncz, block_n, hx, hy, hz, class_id_dev.data_ptr())
+    g._keep = class_id_dev
+    return g
+
+
+def chert_trace_blocks_workspace_bytes(desc, n_classes, grid, n_src, opts):
+    return int(lib().chert_trace_blocks_workspace_bytes(ctypes.byref(desc), n_classes,
+                                                        ctypes.byref(grid), n_src,
+                                                        ctypes.byref(opts)))
+
+
+def chert_trace_blocks(desc, cache_dev, n_classes, grid, mode, src_nodes: Sequence[int], opts,
+                       tau_r=None, tau_i=None, tstar=None, pred_p=None, pred_a=None,
+                       workspace_dev=None, stream=None):
+    src = np.ascontiguousarray(np.asarray(src_nodes, dtype=np.int64).reshape(-1))
+    ws = workspace_dev.numel() * workspace_dev.element_size() if workspace_dev is not None else 0
+    _check(lib().chert_trace_blocks(
         ctypes.byref(desc), _ptr(cache_dev), n_classes, ctypes.byref(grid), mode,
         src.ctypes.data, int(src.size), ctypes.byref(opts), _ptr(tau_r), _ptr(tau_i),
         _ptr(tstar), _ptr(pred_p), _ptr(pred_a), _ptr(workspace_dev), ws, _stream(stream)))

@@ -24,6 +24,12 @@
 // index (the smallest (hop, index) among all tight neighbours), t*_j =
 // t*_pred + the attenuation weight of that segment, each parent's value
 // final one level earlier.
+//
+// 3D (the paper's blocks): the same kernels instantiated for boxes of cn^3
+// lattice intervals whose nodes are the face points, (cn + 1)^3 - (cn - 1)^3
+// <= 64 of them for cn <= 3, one lane each; a block has up to 26 neighbours
+// and a node lies on up to 8 blocks.  Segment columns are the closest
+// Fibonacci direction of the 3D cache.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -36,6 +42,7 @@ namespace chert {
 namespace {
 
 constexpr int kCellMaxN = 16;  // 4 cn boundary nodes <= 64 lanes
+constexpr int kBlockMaxN = 3;  // (cn + 1)^3 - (cn - 1)^3 face nodes <= 64 lanes
 constexpr int kCellWaves = 4;  // waves per workgroup
 constexpr int kCellThreads = 64 * kCellWaves;
 constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;
@@ -102,11 +109,31 @@ __device__ __forceinline__ int cells_of(int gx, int gz, int cn, int ncx, int ncz
   return n;
 }
 
+// the cell indices along one axis whose closed range holds coordinate q
+__device__ __forceinline__ int cells_along(int q, int cn, int nc, int* out) {
+  const int c = q / cn;
+  if (q - c * cn != 0) {
+    out[0] = c;
+    return 1;
+  }
+  int n = 0;
+  if (c - 1 >= 0) out[n++] = c - 1;
+  if (c < nc) out[n++] = c;
+  return n;
+}
+
+struct CellArgs;
+template <bool D3>
+__device__ __forceinline__ int node_cells(const CellArgs& a, int64_t u, int* cs);
+
 struct CellArgs {
   int ncx, ncz, cn, side, NX, K, n_src, n_prob;
+  int ncy, NY;         // 3D: blocks and lattice points along y (2D: 1, 1)
+  int ns, n_off;       // boundary nodes per cell; segment offsets (side^dim)
   int64_t n, C;
   const int32_t* cls;  // lattice -> class
-  const double* W;     // [2][K][K][side^2]
+  const int32_t* slot; // 3D: [ns] local point of slot s, lx | ly << 8 | lz << 16
+  const double* W;     // [2][K][K][n_off]
   double* tau[2];      // per field slot: rows [n_src][n]
   int field_of[2];     // field slot -> 0 (propagation) or 1 (attenuation)
   const int64_t* src;  // [n_src]
@@ -202,16 +229,21 @@ __device__ __forceinline__ double mspm_w(const CellArgs& a, int f, const Rows4& 
 
 // Weight of segment i -> j of cell c (field f): the class-pair table of a
 // cached network, or MSPM's reconstruction from the class table.
-template <bool MSPM>
+template <bool MSPM, bool D3>
 __device__ __forceinline__ double seg_weight(const CellArgs& a, int f, int c, int64_t i,
                                              int64_t j) {
   const int cn = a.cn;
-  const int ix = (int)(i % a.NX), iz = (int)(i / a.NX), jx = (int)(j % a.NX), jz = (int)(j / a.NX);
   if constexpr (!MSPM) {
-    const int64_t s2 = (int64_t)a.side * a.side;
-    const int off = (jz - iz + cn) * a.side + (jx - ix + cn);
-    return a.W[(int64_t)f * a.K * a.K * s2 + ((int64_t)a.cls[i] * a.K + a.cls[j]) * s2 + off];
+    int ix, iy, iz, jx, jy, jz;
+    node_xyz<D3>(a, i, ix, iy, iz);
+    node_xyz<D3>(a, j, jx, jy, jz);
+    const int64_t no = a.n_off;
+    const int off = off_of<D3>(a, jx - ix, jy - iy, jz - iz);
+    return a.W[(int64_t)f * a.K * a.K * no + ((int64_t)a.cls[i] * a.K + a.cls[j]) * no + off];
   } else {
+    static_assert(!D3, "MSPM runs on the 2D cell network");
+    const int ix = (int)(i % a.NX), iz = (int)(i / a.NX), jx = (int)(j % a.NX),
+              jz = (int)(j / a.NX);
     const int x0 = (c % a.ncx) * cn, z0 = (c / a.ncx) * cn;
     const int64_t n00 = (int64_t)x0 + (int64_t)a.NX * z0, dz = (int64_t)a.NX * cn;
     const Rows4 row{(int64_t)a.cls[n00] * a.n_canon, (int64_t)a.cls[n00 + cn] * a.n_canon,
@@ -230,6 +262,79 @@ __device__ __forceinline__ int common_cell(const CellArgs& a, int64_t i, int64_t
     if (ix >= x0 && ix <= x0 + a.cn && iz >= z0 && iz <= z0 + a.cn) return cs[q];
   }
   return cs[0];
+}
+
+// lattice node -> (x, y, z) and back (2D: y = 0)
+template <bool D3>
+__device__ __forceinline__ void node_xyz(const CellArgs& a, int64_t u, int& x, int& y, int& z) {
+  x = (int)(u % a.NX);
+  const int64_t r = u / a.NX;
+  if constexpr (D3) {
+    y = (int)(r % a.NY);
+    z = (int)(r / a.NY);
+  } else {
+    y = 0;
+    z = (int)r;
+  }
+}
+__device__ __forceinline__ int64_t node_at(const CellArgs& a, int x, int y, int z) {
+  return (int64_t)x + (int64_t)a.NX * ((int64_t)y + (int64_t)a.NY * z);
+}
+
+// the cells (blocks) whose boundary holds lattice node u: at most 4 (8)
+template <bool D3>
+__device__ __forceinline__ int node_cells(const CellArgs& a, int64_t u, int* cs) {
+  int x, y, z;
+  node_xyz<D3>(a, u, x, y, z);
+  if constexpr (!D3) {
+    return cells_of(x, z, a.cn, a.ncx, a.ncz, cs);
+  } else {
+    int xs[2], ys[2], zs[2];
+    const int nx = cells_along(x, a.cn, a.ncx, xs), ny = cells_along(y, a.cn, a.ncy, ys),
+              nz = cells_along(z, a.cn, a.ncz, zs);
+    int n = 0;
+    for (int i = 0; i < nx; ++i)
+      for (int j = 0; j < ny; ++j)
+        for (int k = 0; k < nz; ++k) cs[n++] = xs[i] + a.ncx * (ys[j] + a.ncy * zs[k]);
+    return n;
+  }
+}
+
+// local point of boundary slot s of a cell (block)
+template <bool D3>
+__device__ __forceinline__ void slot_pos(const CellArgs& a, int s, int& lx, int& ly, int& lz) {
+  if constexpr (!D3) {
+    slot_xy(s, a.cn, lx, lz);
+    ly = 0;
+  } else {
+    const int q = a.slot[s];
+    lx = q & 255;
+    ly = (q >> 8) & 255;
+    lz = q >> 16;
+  }
+}
+
+// origin (lattice point of the lowest corner) of cell (block) c
+template <bool D3>
+__device__ __forceinline__ void cell_origin(const CellArgs& a, int c, int& x0, int& y0, int& z0) {
+  x0 = (c % a.ncx) * a.cn;
+  if constexpr (D3) {
+    const int r = c / a.ncx;
+    y0 = (r % a.ncy) * a.cn;
+    z0 = (r / a.ncy) * a.cn;
+  } else {
+    y0 = 0;
+    z0 = (c / a.ncx) * a.cn;
+  }
+}
+
+// segment offset index: (dz, dx) in 2D, (dz, dy, dx) in 3D, each in [-cn, cn]
+template <bool D3>
+__device__ __forceinline__ int off_of(const CellArgs& a, int dx, int dy, int dz) {
+  if constexpr (D3)
+    return ((dz + a.cn) * a.side + (dy + a.cn)) * a.side + (dx + a.cn);
+  else
+    return (dz + a.cn) * a.side + (dx + a.cn);
 }
 
 __device__ __forceinline__ double* tau_row(const CellArgs& a, int p) {
@@ -280,8 +385,9 @@ __global__ void k_cell_seed(CellArgs a) {
   const int fi = p / a.n_src, s = p - fi * a.n_src;
   const int64_t src = a.src[s];
   tau_row(a, p)[src] = 0.0;
-  int cs[4];
-  const int nc = cells_of((int)(src % a.NX), (int)(src / a.NX), a.cn, a.ncx, a.ncz, cs);
+  int cs[8];
+  const int nc = a.NY > 1 ? node_cells<true>(a, src, cs)  // 3D blocks
+                           : node_cells<false>(a, src, cs);
   for (int q = 0; q < nc; ++q) {
     a.active[(int64_t)p * a.C + cs[q]] = 1;
     a.key[(int64_t)p * a.C + cs[q]] = 0ull;
@@ -349,19 +455,21 @@ __global__ void k_cell_select(CellArgs a, int r) {
 // round r, step 3: relax the listed cells.  Each visit first stages the
 // weights of its ns x ns ordered pairs in LDS (one batch of independent
 // loads per lane), then runs the passes from LDS and lane broadcasts.
-template <bool MSPM>
+template <bool MSPM, bool D3>
 __global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) {
+  static_assert(!(MSPM && D3), "MSPM runs on the 2D cell network");
+  constexpr int NNB = D3 ? 26 : 8;  // neighbouring cells (blocks)
   // dynamic LDS: [the class-pair table, when it fits][waves][ns][ns]
   extern __shared__ double s_w[];
-  __shared__ unsigned long long s_wake[kCellWaves][8];  // per neighbour cell
+  __shared__ unsigned long long s_wake[kCellWaves][NNB];  // per neighbour cell
   const int lane = threadIdx.x & 63;
   const int wib = threadIdx.x >> 6;
   const int wpb = blockDim.x >> 6;
   const int wave = blockIdx.x * wpb + wib;
   const int nw = gridDim.x * wpb;
   const int count = a.count[r & 1];
-  const int cn = a.cn, ns = 4 * cn, side = a.side, K = a.K;
-  const int64_t s2 = (int64_t)side * side;
+  const int cn = a.cn, ns = D3 ? a.ns : 4 * cn, K = a.K;
+  const int64_t s2 = a.n_off;
   const int64_t tab_n = a.w_lds ? 2LL * K * K * s2 : 0;
   double* wl = s_w + tab_n + (size_t)wib * ns * ns;
   // the whole class-pair table of both fields in LDS, once per workgroup
@@ -370,19 +478,19 @@ __global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) 
     for (int64_t q = threadIdx.x; q < tab_n; q += blockDim.x) s_w[q] = a.W[q];
     __syncthreads();
   }
-  int lx = 0, lz = 0;
-  if (lane < ns) slot_xy(lane, cn, lx, lz);
+  int lx = 0, ly = 0, lz = 0;
+  if (lane < ns) slot_pos<D3>(a, lane, lx, ly, lz);
   unsigned long long visits = 0, pairs = 0, passes_all = 0;
   for (int it = wave; it < count; it += nw) {
     const int64_t item = a.list[it];
     const int p = (int)(item / a.C);
     const int c = (int)(item - (int64_t)p * a.C);
-    const int cx = c % a.ncx, cz = c / a.ncx;
+    int x0, y0, z0;
+    cell_origin<D3>(a, c, x0, y0, z0);
     double* tau = tau_row(a, p);
     const double* W =
         a.W ? (a.w_lds ? s_w : a.W) + (int64_t)a.field_of[p / a.n_src] * K * K * s2 : nullptr;
-    const int gx = cx * cn + lx, gz = cz * cn + lz;
-    const int64_t node = (int64_t)gx + (int64_t)a.NX * gz;
+    const int64_t node = node_at(a, x0 + lx, y0 + ly, z0 + lz);
     int k = 0;
     double t = INFINITY;
     if (lane < ns) {
@@ -411,8 +519,9 @@ __global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) 
           const int sa = sa0 + u < ns ? sa0 + u : ns - 1;
           const int ka = __builtin_amdgcn_readlane(k, sa);
           const int ax = __builtin_amdgcn_readlane(lx, sa);
+          const int ay = D3 ? __builtin_amdgcn_readlane(ly, sa) : 0;
           const int az = __builtin_amdgcn_readlane(lz, sa);
-          const int off = (lz - az + cn) * side + (lx - ax + cn);
+          const int off = off_of<D3>(a, lx - ax, ly - ay, lz - az);
           w8[u] = lane < ns ? Wk[(int64_t)ka * K * s2 + off] : 0.0;
         }
 #pragma unroll
@@ -442,35 +551,46 @@ __global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) 
     ++visits;
     pairs += (unsigned long long)passes * ns * (ns - 1);
     passes_all += passes;
-    // lower the improved nodes; each of the 8 neighbouring cells is woken
-    // once, with the smallest new traveltime among the nodes it shares
-    if (lane < 8) s_wake[wib][lane] = kInfBits;
+    // lower the improved nodes; each of the neighbouring cells (8, or 26
+    // blocks) is woken once, with the smallest new traveltime among the nodes
+    // it shares
+    if (lane < NNB) s_wake[wib][lane] = kInfBits;
     wave_sync_lds();
     // (the atomic's old value is not waited for: a node this visit lowered
     // wakes its other cells even if another visit lowered it further, which
     // costs at most a visit that changes nothing)
+    constexpr int kSelf = D3 ? 13 : 4;  // index of the cell itself
     if (lane < ns && t < t0) {
       const unsigned long long nb = dbits(t);
       atomicMin((unsigned long long*)&tau[node], nb);
       {
         const int ex = lx == 0 ? -1 : (lx == cn ? 1 : 0);
+        const int ey = D3 ? (ly == 0 ? -1 : (ly == cn ? 1 : 0)) : 0;
         const int ez = lz == 0 ? -1 : (lz == cn ? 1 : 0);
-        // neighbour d = (dx + 1) + 3 (dz + 1), skipping the cell itself
+        // neighbour d = (dx + 1) + 3 (dy + 1) + 9 (dz + 1) (2D: (dx + 1) +
+        // 3 (dz + 1)), skipping the cell itself
         for (int dz = -1; dz <= 1; ++dz)
-          for (int dx = -1; dx <= 1; ++dx) {
-            if ((dx == 0 && dz == 0) || (dx != 0 && dx != ex) || (dz != 0 && dz != ez)) continue;
-            const int d = (dx + 1) + 3 * (dz + 1);
-            atomicMin(&s_wake[wib][d < 4 ? d : d - 1], nb);
-          }
+          for (int dy = D3 ? -1 : 0; dy <= (D3 ? 1 : 0); ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+              if ((dx == 0 && dy == 0 && dz == 0) || (dx != 0 && dx != ex) ||
+                  (dy != 0 && dy != ey) || (dz != 0 && dz != ez))
+                continue;
+              const int d = D3 ? (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1) : (dx + 1) + 3 * (dz + 1);
+              atomicMin(&s_wake[wib][d < kSelf ? d : d - 1], nb);
+            }
       }
     }
     wave_sync_lds();
-    if (lane < 8) {
+    if (lane < NNB) {
       const unsigned long long v = s_wake[wib][lane];
-      const int d = lane < 4 ? lane : lane + 1;
-      const int nx = cx + d % 3 - 1, nz = cz + d / 3 - 1;
-      if (v != kInfBits && nx >= 0 && nx < a.ncx && nz >= 0 && nz < a.ncz) {
-        const int64_t e = (int64_t)p * a.C + nx + (int64_t)a.ncx * nz;
+      const int d = lane < kSelf ? lane : lane + 1;
+      const int cx = x0 / cn, cy = y0 / cn, cz = z0 / cn;
+      const int nx = cx + d % 3 - 1;
+      const int ny = D3 ? cy + (d / 3) % 3 - 1 : 0;
+      const int nz = D3 ? cz + d / 9 - 1 : cz + d / 3 - 1;
+      if (v != kInfBits && nx >= 0 && nx < a.ncx && ny >= 0 && ny < a.ncy && nz >= 0 &&
+          nz < a.ncz) {
+        const int64_t e = (int64_t)p * a.C + nx + (int64_t)a.ncx * (ny + (int64_t)a.ncy * nz);
         atomicMin(&a.key[e], v);
         a.active[e] = 1;
         if (a.bucket > 0.0) atomicMin(&a.minkey[(int64_t)((r + 1) % 3) * a.n_prob + p], v);
@@ -495,8 +615,9 @@ __global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) 
 // when the previous launch ended): pred_j and t*_j = t*_pred + the
 // attenuation weight of that segment (the parent's value final one level
 // earlier).  Level bounds rotate through three slots per problem.
-template <bool MSPM>
+template <bool MSPM, bool D3>
 __global__ void __launch_bounds__(256) k_cell_level(CellArgs a, int L) {
+  static_assert(!(MSPM && D3), "MSPM runs on the 2D cell network");
   const int p = blockIdx.y;
   const int fi = p / a.n_src, s = p - fi * a.n_src;
   if (!((a.tree_mask >> fi) & 1)) return;
@@ -509,8 +630,9 @@ __global__ void __launch_bounds__(256) k_cell_level(CellArgs a, int L) {
     a.cnt[((L + 1) % 3) * P + p] = 0;
   }
   int32_t* cnt = a.cnt + (L % 3) * P + p;
-  const int cn = a.cn, ns = 4 * cn;
-  const int per = 4 * ns;  // (cell, slot) triples per node
+  const int ns = D3 ? a.ns : 4 * a.cn;
+  constexpr int kCells = D3 ? 8 : 4;  // cells (blocks) a node can lie on
+  const int per = kCells * ns;        // (cell, slot) triples per node
   const int f = a.field_of[fi];
   const double* tau = a.tau[fi] + (int64_t)s * a.n;
   int32_t* hop = a.hop + (int64_t)p * a.n;
@@ -524,23 +646,22 @@ __global__ void __launch_bounds__(256) k_cell_level(CellArgs a, int L) {
   const int64_t work = (int64_t)(end - start) * per;
   for (int64_t t = tid; t < work; t += nthr) {
     const int64_t j = bfs[start + (int)(t / per)];
-    const int q = (int)((t / ns) & 3), sl = (int)(t % ns);
-    const int jx = (int)(j % a.NX), jz = (int)(j / a.NX);
-    int cs[4];
-    const int nc = cells_of(jx, jz, cn, a.ncx, a.ncz, cs);
+    const int q = (int)((t / ns) & (kCells - 1)), sl = (int)(t % ns);
+    int cs[kCells];
+    const int nc = node_cells<D3>(a, j, cs);
     if (q >= nc) continue;
-    int lx, lz;
-    slot_xy(sl, cn, lx, lz);
-    const int vx = (cs[q] % a.ncx) * cn + lx, vz = (cs[q] / a.ncx) * cn + lz;
-    const int64_t v = (int64_t)vx + (int64_t)a.NX * vz;
+    int lx, ly, lz, x0, y0, z0;
+    slot_pos<D3>(a, sl, lx, ly, lz);
+    cell_origin<D3>(a, cs[q], x0, y0, z0);
+    const int64_t v = node_at(a, x0 + lx, y0 + ly, z0 + lz);
     if (v == j) continue;
     const double tj = tau[j], tv = tau[v];
     const int hv = hop[v];
     if (L > 0 && hv == L - 1) {  // v -> j tight?
-      if (tv + seg_weight<MSPM>(a, f, cs[q], v, j) == tj) atomicMin(&bid[j], (int)v);
+      if (tv + seg_weight<MSPM, D3>(a, f, cs[q], v, j) == tj) atomicMin(&bid[j], (int)v);
     }
     if (hv == -1 && tv < INFINITY) {  // j -> v tight?
-      if (tj + seg_weight<MSPM>(a, f, cs[q], j, v) == tv &&
+      if (tj + seg_weight<MSPM, D3>(a, f, cs[q], j, v) == tv &&
           atomicCAS(&hop[v], -1, L + 1) == -1) {
         bfs[end + atomicAdd(cnt, 1)] = (int32_t)v;
         ++added;
@@ -556,7 +677,7 @@ __global__ void __launch_bounds__(256) k_cell_level(CellArgs a, int L) {
       // in bounds
       if (b == 0x7fffffff) continue;
       if (pred) pred[j] = b;
-      if (ts) ts[j] = ts[b] + seg_weight<MSPM>(a, 1, MSPM ? common_cell(a, b, j) : 0, b, j);
+      if (ts) ts[j] = ts[b] + seg_weight<MSPM, D3>(a, 1, MSPM ? common_cell(a, b, j) : 0, b, j);
     }
   }
   for (int o = 32; o > 0; o >>= 1) added += __shfl_xor(added, o);
@@ -564,6 +685,38 @@ __global__ void __launch_bounds__(256) k_cell_level(CellArgs a, int L) {
 }
 
 __global__ void k_cell_zero(int32_t* x) { *x = 0; }
+
+// 3D segment columns: one wave per offset o, the Fibonacci direction with
+// the largest dot product f . u_o (IEEE operations in the order of the
+// definition, no contraction), the lowest index among equals: each lane
+// keeps its first strict maximum over a strided pass, then the wave merges
+// (larger dot first, lower index on a tie), which is the sequential rule.
+__global__ void __launch_bounds__(256) k_fib_nearest(const double* f, int N, const double* u,
+                                                     int n_off, int32_t* col) {
+  const int o = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (o >= n_off) return;
+  const int lane = threadIdx.x & 63;
+  const double u0 = u[3 * o], u1 = u[3 * o + 1], u2 = u[3 * o + 2];
+  double bd = -2.0;
+  int bi = 0x7fffffff;
+  for (int i = lane; i < N; i += 64) {
+    const double d = __dadd_rn(__dadd_rn(__dmul_rn(f[3 * i], u0), __dmul_rn(f[3 * i + 1], u1)),
+                               __dmul_rn(f[3 * i + 2], u2));
+    if (d > bd) {
+      bd = d;
+      bi = i;
+    }
+  }
+  for (int w = 32; w > 0; w >>= 1) {
+    const double od = __shfl_xor(bd, w);
+    const int oi = __shfl_xor(bi, w);
+    if (od > bd || (od == bd && oi < bi)) {
+      bd = od;
+      bi = oi;
+    }
+  }
+  if (lane == 0) col[o] = bi;
+}
 
 // ---------------------------------------------------------------- plan ----
 
@@ -616,56 +769,105 @@ struct CellSrc {
   int kernel = 0, n_sweep = 0;
 };
 
+// The network's geometry: 2D cells (chert_cell_grid) or 3D blocks
+// (chert_block_grid); ncy = 1, hy = 0 in 2D.
+struct CellGeo {
+  int dim = 2;
+  int ncx = 0, ncy = 1, ncz = 0, cn = 0;
+  double hx = 0.0, hy = 0.0, hz = 0.0;
+  const int32_t* cls = nullptr;
+};
+
+CellGeo geo_of(const chert_cell_grid* g) {
+  CellGeo G;
+  G.dim = 2;
+  G.ncx = g->ncx;
+  G.ncz = g->ncz;
+  G.cn = g->cell_n;
+  G.hx = g->hx;
+  G.hz = g->hz;
+  G.cls = g->class_id_dev;
+  return G;
+}
+
+CellGeo geo_of(const chert_block_grid* g) {
+  CellGeo G;
+  G.dim = 3;
+  G.ncx = g->ncx;
+  G.ncy = g->ncy;
+  G.ncz = g->ncz;
+  G.cn = g->block_n;
+  G.hx = g->hx;
+  G.hy = g->hy;
+  G.hz = g->hz;
+  G.cls = g->class_id_dev;
+  return G;
+}
+
 struct CellPlan {
-  int cn = 0, side = 0, NX = 0, NZ = 0, n_prob = 0, nfs = 0, max_rounds = 0, n_cols = 0;
-  int n_canon = 0;
+  int dim = 2, cn = 0, side = 0, NX = 0, NY = 1, NZ = 0, n_prob = 0, nfs = 0, max_rounds = 0;
+  int n_cols = 0, n_canon = 0, ns = 0, n_off = 0, N = 0;
   int64_t n = 0, C = 0, K = 0;
   int fields[2] = {0, 0};
   bool slow = false;
-  size_t off_tab = 0, off_W = 0, off_best = 0, off_ctl = 0, off_src = 0, off_act = 0,
-         off_key = 0, off_list = 0, off_hop = 0, off_bfs = 0, off_bid = 0, off_kt = 0,
-         off_vt = 0, off_jobs = 0, total = 0;
+  size_t off_tab = 0, off_geo = 0, off_W = 0, off_best = 0, off_ctl = 0, off_src = 0,
+         off_act = 0, off_key = 0, off_list = 0, off_hop = 0, off_bfs = 0, off_bid = 0,
+         off_kt = 0, off_vt = 0, off_jobs = 0, total = 0;
 };
 
-int cell_plan(const CellSrc& w, int64_t n_classes, const chert_cell_grid* g, int32_t mode,
+int cell_plan(const CellSrc& w, int64_t n_classes, const CellGeo& G, int32_t mode,
               const int64_t* src, int32_t n_src, const chert_trace_opts* o, CellPlan* P) {
-  if (!g || !o) return fail(CHERT_ERR_INVALID_ARG, "null grid or options");
+  if (!o) return fail(CHERT_ERR_INVALID_ARG, "null options");
+  P->dim = G.dim;
   if (!w.mspm) {
     const chert_cache_desc* d = w.d;
     if (!d) return fail(CHERT_ERR_INVALID_ARG, "null descriptor");
     chert_cache_layout lay;
     int rc = chert_cache_layout_of(d, n_classes, &lay);
     if (rc) return rc;
-    if (d->dim != 2) return fail(CHERT_ERR_INVALID_ARG, "cell networks are 2D");
+    if (d->dim != G.dim)
+      return fail(CHERT_ERR_INVALID_ARG,
+                  G.dim == 2 ? "cell networks take 2D caches" : "block networks take 3D caches");
     if (mode < 0 || mode > 2 || !(d->mode_mask & (1u << mode)))
       return fail(CHERT_ERR_INVALID_ARG, "mode not in the cache");
     P->slow = d->sampling == CHERT_SAMPLE_SLOWNESS;
     P->n_cols = d->n_subset ? d->n_subset : d->n_dirs;
+    P->N = G.dim == 3 ? d->n_dirs : 0;
   } else {
+    if (G.dim != 2) return fail(CHERT_ERR_UNSUPPORTED, "MSPM runs on the 2D cell network");
     if (mode < 0 || mode > 2) return fail(CHERT_ERR_INVALID_ARG, "mode must be 0..2");
     if (w.kernel != CHERT_KERNEL_MEV && w.kernel != CHERT_KERNEL_OEV)
       return fail(CHERT_ERR_INVALID_ARG, "kernel must be MEV or OEV");
     if (w.n_sweep < 8 || w.n_sweep > kMaxSweep)
       return fail(CHERT_ERR_INVALID_ARG, "n_sweep must be 8..4096");
   }
-  if (g->ncx < 1 || g->ncz < 1) return fail(CHERT_ERR_INVALID_ARG, "need at least one cell");
-  if (g->cell_n < 1 || g->cell_n > kCellMaxN)
+  if (G.ncx < 1 || G.ncy < 1 || G.ncz < 1)
+    return fail(CHERT_ERR_INVALID_ARG, "need at least one cell");
+  if (G.dim == 2 && (G.cn < 1 || G.cn > kCellMaxN))
     return fail(CHERT_ERR_INVALID_ARG, "cell_n must be 1..16");
-  if (!(g->hx > 0.0) || !(g->hz > 0.0) || !isfinite(g->hx) || !isfinite(g->hz))
+  if (G.dim == 3 && (G.cn < 1 || G.cn > kBlockMaxN))
+    return fail(CHERT_ERR_INVALID_ARG, "block_n must be 1..3");
+  if (!(G.hx > 0.0) || !(G.hz > 0.0) || !isfinite(G.hx) || !isfinite(G.hz) ||
+      (G.dim == 3 && (!(G.hy > 0.0) || !isfinite(G.hy))))
     return fail(CHERT_ERR_INVALID_ARG, "spacing must be positive and finite");
-  if (!g->class_id_dev) return fail(CHERT_ERR_INVALID_ARG, "cell networks need a class map");
-  P->cn = g->cell_n;
+  if (!G.cls) return fail(CHERT_ERR_INVALID_ARG, "cell networks need a class map");
+  P->cn = G.cn;
   P->side = 2 * P->cn + 1;
   P->n_canon = 2 * P->cn * (P->cn + 1);
-  const int64_t NX = (int64_t)g->ncx * P->cn + 1, NZ = (int64_t)g->ncz * P->cn + 1;
-  if (NX * NZ >= 0x7fffffffLL) return fail(CHERT_ERR_INVALID_ARG, "lattice too large");
+  P->n_off = G.dim == 3 ? P->side * P->side * P->side : P->side * P->side;
+  P->ns = G.dim == 3 ? (P->cn + 1) * (P->cn + 1) * (P->cn + 1) - (P->cn - 1) * (P->cn - 1) * (P->cn - 1)
+                     : 4 * P->cn;
+  const int64_t NX = (int64_t)G.ncx * P->cn + 1, NZ = (int64_t)G.ncz * P->cn + 1;
+  const int64_t NY = G.dim == 3 ? (int64_t)G.ncy * P->cn + 1 : 1;
+  if (NX * NY * NZ >= 0x7fffffffLL) return fail(CHERT_ERR_INVALID_ARG, "lattice too large");
   P->NX = (int)NX;
+  P->NY = (int)NY;
   P->NZ = (int)NZ;
-  P->n = NX * NZ;
-  P->C = (int64_t)g->ncx * g->ncz;
+  P->n = NX * NY * NZ;
+  P->C = (int64_t)G.ncx * G.ncy * G.ncz;
   P->K = n_classes;
   if (n_classes < 1) return fail(CHERT_ERR_INVALID_ARG, "need at least one class");
-  if (n_classes * n_classes * P->side * P->side >= 0x7fffffffLL)
+  if (n_classes * n_classes * P->n_off >= 0x7fffffffLL)
     return fail(CHERT_ERR_UNSUPPORTED, "class-pair table too large");
   const uint32_t outs = o->outputs;
   if (outs == 0 || (outs & ~31u) || !(outs & (CHERT_OUT_TAU_R | CHERT_OUT_TAU_I)))
@@ -681,8 +883,8 @@ int cell_plan(const CellSrc& w, int64_t n_classes, const chert_cell_grid* g, int
   if (n_src < 1 || !src) return fail(CHERT_ERR_INVALID_ARG, "need sources");
   for (int i = 0; i < n_src; ++i) {
     if (src[i] < 0 || src[i] >= P->n) return fail(CHERT_ERR_INVALID_ARG, "source out of range");
-    const int64_t x = src[i] % NX, z = src[i] / NX;
-    if (x % P->cn != 0 && z % P->cn != 0)
+    const int64_t x = src[i] % NX, y = (src[i] / NX) % NY, z = src[i] / (NX * NY);
+    if (x % P->cn != 0 && z % P->cn != 0 && (G.dim == 2 || y % P->cn != 0))
       return fail(CHERT_ERR_INVALID_ARG, "a source inside a cell is not a node");
   }
   P->nfs = 0;
@@ -692,13 +894,16 @@ int cell_plan(const CellSrc& w, int64_t n_classes, const chert_cell_grid* g, int
   P->n_prob = P->nfs * n_src;
   if ((int64_t)P->n_prob * P->C >= 0x7fffffffLL / 4 || (int64_t)P->n_prob * P->n >= (1LL << 40))
     return fail(CHERT_ERR_UNSUPPORTED, "batch too large for one call");
-  P->max_rounds = o->max_rounds > 0 ? o->max_rounds : 4096 + 64 * (g->ncx + g->ncz);
-  const int s2 = P->side * P->side;
+  P->max_rounds =
+      o->max_rounds > 0 ? o->max_rounds : 4096 + 64 * (G.ncx + (G.dim == 3 ? G.ncy : 0) + G.ncz);
+  const int s2 = P->n_off;
   const size_t q3 = 2 * sizeof(double) + sizeof(int32_t);  // V, A, status
   size_t off = 0;
   P->off_tab = off;  // L (double), ox, oz, col, canon (int32), psi (double)
   off += al256((size_t)s2 * (sizeof(double) + 4 * sizeof(int32_t)) +
                (size_t)P->n_canon * sizeof(double) + 8);
+  P->off_geo = off;  // 3D: unit vectors [n_off][3], Fibonacci directions [N][3], slots [64]
+  if (G.dim == 3) off += al256((size_t)3 * (s2 + P->N) * sizeof(double) + 64 * sizeof(int32_t));
   P->off_W = off;
   if (!w.mspm) off += al256((size_t)2 * n_classes * n_classes * s2 * sizeof(double));
   P->off_best = off;
@@ -730,24 +935,24 @@ int cell_plan(const CellSrc& w, int64_t n_classes, const chert_cell_grid* g, int
   return CHERT_OK;
 }
 
-size_t cell_workspace(const CellSrc& w, int64_t n_classes, const chert_cell_grid* g,
-                      int32_t n_src, const chert_trace_opts* o) {
-  if (!g || n_src < 1) return 0;
+size_t cell_workspace(const CellSrc& w, int64_t n_classes, const CellGeo& G, int32_t n_src,
+                      const chert_trace_opts* o) {
+  if (n_src < 1) return 0;
   // sources are checked by the trace call; a lattice corner stands in here
   std::vector<int64_t> src((size_t)n_src, 0);
   CellPlan P;
   for (int m = 0; m < 3; ++m)  // the mode is checked by the trace call
-    if (cell_plan(w, n_classes, g, m, src.data(), n_src, o, &P) == CHERT_OK) return P.total;
+    if (cell_plan(w, n_classes, G, m, src.data(), n_src, o, &P) == CHERT_OK) return P.total;
   return 0;
 }
 
-int trace_cells_impl(const CellSrc& w, int64_t n_classes, const chert_cell_grid* g,
-                     int32_t mode, const int64_t* src_nodes_host, int32_t n_src,
-                     const chert_trace_opts* o, double* tau_r_dev, double* tau_i_dev,
-                     double* tstar_dev, int32_t* pred_p_dev, int32_t* pred_a_dev,
-                     void* workspace_dev, size_t workspace_bytes, void* stream) {
+int trace_cells_impl(const CellSrc& w, int64_t n_classes, const CellGeo& G, int32_t mode,
+                     const int64_t* src_nodes_host, int32_t n_src, const chert_trace_opts* o,
+                     double* tau_r_dev, double* tau_i_dev, double* tstar_dev, int32_t* pred_p_dev,
+                     int32_t* pred_a_dev, void* workspace_dev, size_t workspace_bytes,
+                     void* stream) {
   CellPlan P;
-  int rc = cell_plan(w, n_classes, g, mode, src_nodes_host, n_src, o, &P);
+  int rc = cell_plan(w, n_classes, G, mode, src_nodes_host, n_src, o, &P);
   if (rc) return rc;
   const uint32_t outs = o->outputs;
   if (!w.mspm && !w.cache_dev) return fail(CHERT_ERR_INVALID_ARG, "null cache");
@@ -761,42 +966,76 @@ int trace_cells_impl(const CellSrc& w, int64_t n_classes, const chert_cell_grid*
     return fail(CHERT_ERR_INVALID_ARG, "workspace too small or unaligned");
   hipStream_t s = (hipStream_t)stream;
   uint8_t* ws = (uint8_t*)workspace_dev;
-  const int cn = P.cn, side = P.side, s2 = side * side;
+  const int cn = P.cn, side = P.side, s2 = P.n_off;
   const int K = (int)P.K;
 
   // segment offsets (dx, dz) in [-cn, cn]^2 (the centre is never a segment:
   // a stand-in offset keeps the lookups finite), lengths (eq 27), columns;
   // MSPM: canonical offsets (direction angle in [0, pi)) and their exact
-  // global ray angles
+  // global ray angles.  3D: offsets (dx, dy, dz) in [-cn, cn]^3, lengths and
+  // unit vectors (the columns come from k_fib_nearest), and the block's face
+  // points as slots.
   std::vector<int32_t> tab((size_t)s2 * 4);
   std::vector<double> L((size_t)s2), psi((size_t)P.n_canon), Lc((size_t)P.n_canon);
-  for (int dz = -cn; dz <= cn; ++dz)
+  std::vector<double> geo;
+  std::vector<int32_t> slots;
+  if (P.dim == 3) {
+    geo.assign((size_t)3 * (s2 + P.N), 0.0);
+    for (int dz = -cn; dz <= cn; ++dz)
+      for (int dy = -cn; dy <= cn; ++dy)
+        for (int dx = -cn; dx <= cn; ++dx) {
+          const int q = ((dz + cn) * side + (dy + cn)) * side + (dx + cn);
+          tab[q] = 0;
+          tab[s2 + q] = 0;
+          tab[2 * s2 + q] = 0;
+          tab[3 * s2 + q] = -1;
+          if (dx == 0 && dy == 0 && dz == 0) {  // never a segment
+            L[q] = 0.0;
+            geo[3 * q + 2] = 1.0;
+            continue;
+          }
+          const double ex = dx * G.hx, ey = dy * G.hy, ez = dz * G.hz;
+          const double len = sqrt(ex * ex + ez * ez + ey * ey);  // eq 27 in 3D
+          L[q] = len;
+          geo[3 * q] = ex / len;
+          geo[3 * q + 1] = ey / len;
+          geo[3 * q + 2] = ez / len;
+        }
+    fibonacci(P.N, geo.data() + 3 * (size_t)s2);
+    for (int z = 0; z <= cn; ++z)
+      for (int y = 0; y <= cn; ++y)
+        for (int x = 0; x <= cn; ++x)
+          if (x == 0 || y == 0 || z == 0 || x == cn || y == cn || z == cn)
+            slots.push_back(x | (y << 8) | (z << 16));
+    if ((int)slots.size() != P.ns) return fail(CHERT_ERR_INVALID_ARG, "block slot count");
+  }
+  for (int dz = -cn; dz <= cn && P.dim == 2; ++dz)
     for (int dx = -cn; dx <= cn; ++dx) {
       const int q = (dz + cn) * side + (dx + cn);
       const int x = (dx == 0 && dz == 0) ? 1 : dx;
       tab[q] = x;
       tab[s2 + q] = dz;
-      const double ex = x * g->hx, ez = dz * g->hz;
+      const double ex = x * G.hx, ez = dz * G.hz;
       L[q] = sqrt(ex * ex + ez * ez);
       tab[2 * s2 + q] = 0;
       tab[3 * s2 + q] = -1;
     }
-  {
+  if (P.dim == 2) {
     int ci = 0;
     for (int dz = -cn; dz <= cn; ++dz)
       for (int dx = -cn; dx <= cn; ++dx) {
         if (!(dx > 0 || (dx == 0 && dz > 0))) continue;
-        psi[ci] = atan2(dx * g->hx, dz * g->hz);
+        psi[ci] = atan2(dx * G.hx, dz * G.hz);
         Lc[ci] = L[(dz + cn) * side + (dx + cn)];
         tab[3 * s2 + (dz + cn) * side + (dx + cn)] = ci;
         tab[3 * s2 + (-dz + cn) * side + (-dx + cn)] = ci;
         ++ci;
       }
   }
-  if (!w.mspm && !P.slow) {
+  if (!w.mspm && !P.slow && P.dim == 2) {
     std::vector<int32_t> bin((size_t)s2);
     for (int q = 0; q < s2; ++q)
-      bin[q] = star_bin_2d(tab[q], tab[s2 + q], g->hx, g->hz, w.d->n_dirs);
+      bin[q] = star_bin_2d(tab[q], tab[s2 + q], G.hx, G.hz, w.d->n_dirs);
     rc = star_columns(w.d, bin.data(), s2, tab.data() + 2 * s2);
     if (rc) return rc;
   }
@@ -813,22 +1052,37 @@ int trace_cells_impl(const CellSrc& w, int64_t n_classes, const chert_cell_grid*
                        hipMemcpyHostToDevice, s);
   if (e == hipSuccess && w.mspm)
     e = hipMemcpyAsync(dpsi, psi.data(), psi.size() * sizeof(double), hipMemcpyHostToDevice, s);
+  double* dgeo = (double*)(ws + P.off_geo);
+  int32_t* dslot = (int32_t*)(dgeo + 3 * ((size_t)s2 + P.N));
+  if (e == hipSuccess && P.dim == 3)
+    e = hipMemcpyAsync(dgeo, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && P.dim == 3)
+    e = hipMemcpyAsync(dslot, slots.data(), slots.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                       s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // host buffers are locals
   if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+  if (P.dim == 3)  // the closest Fibonacci direction of every offset
+    CHERT_LAUNCH("k_fib_nearest", k_fib_nearest, dim3((unsigned)((s2 + 3) / 4)), dim3(256), 0, s,
+                 dgeo + 3 * (size_t)s2, P.N, dgeo, s2, dtab + 2 * s2);
 
   uint8_t* ctl = ws + P.off_ctl;
   CellArgs a{};
-  a.ncx = g->ncx;
-  a.ncz = g->ncz;
+  a.ncx = G.ncx;
+  a.ncy = G.ncy;
+  a.ncz = G.ncz;
   a.cn = cn;
   a.side = side;
   a.NX = P.NX;
+  a.NY = P.NY;
+  a.ns = P.ns;
+  a.n_off = P.n_off;
+  a.slot = P.dim == 3 ? dslot : nullptr;
   a.K = K;
   a.n_src = n_src;
   a.n_prob = P.n_prob;
   a.n = P.n;
   a.C = P.C;
-  a.cls = g->class_id_dev;
+  a.cls = G.cls;
   a.W = w.mspm ? nullptr : (const double*)(ws + P.off_W);
   a.src = dsrc;
   a.count = (int32_t*)ctl;
@@ -876,7 +1130,7 @@ int trace_cells_impl(const CellSrc& w, int64_t n_classes, const chert_cell_grid*
 
   // class ids checked before any output is written
   CHERT_LAUNCH("k_cell_zero", k_cell_zero, dim3(1), dim3(1), 0, s, err);
-  enqueue_class_check(g->class_id_dev, P.n, K, err, s);
+  enqueue_class_check(G.cls, P.n, K, err, s);
   {
     int32_t herr = 0;
     e = hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
@@ -899,8 +1153,8 @@ int trace_cells_impl(const CellSrc& w, int64_t n_classes, const chert_cell_grid*
     if (P.slow) {
       best = (int32_t*)(ws + P.off_best);
       enqueue_slow_lookup(best, K, P.n_cols, fields + CHERT_F_RX * ent + mslice,
-                          fields + CHERT_F_RZ * ent + mslice, Sm, s2, dtab, dtab + s2, g->hx,
-                          g->hz, s);
+                          fields + CHERT_F_RZ * ent + mslice, Sm, s2, dtab, dtab + s2, G.hx,
+                          G.hz, s);
     }
     enqueue_pair_weights((double*)(ws + P.off_W), K, s2, fields + CHERT_F_V * ent + mslice,
                          fields + CHERT_F_A * ent + mslice, Sm, P.n_cols, dL, dtab + 2 * s2,
@@ -933,7 +1187,7 @@ int trace_cells_impl(const CellSrc& w, int64_t n_classes, const chert_cell_grid*
   const unsigned gsel = (unsigned)((items + 255) / 256 > 2048 ? 2048 : (items + 255) / 256);
   // waves per workgroup: the staged pair weights (ns^2 doubles per wave)
   // within 64 KiB of LDS
-  const int ns = 4 * cn;
+  const int ns = P.ns;
   int wpb = (int)(65536 / ((size_t)ns * ns * sizeof(double)));
   if (wpb > kCellWaves) wpb = kCellWaves;
   if (wpb < 1) wpb = 1;
@@ -959,11 +1213,14 @@ int trace_cells_impl(const CellSrc& w, int64_t n_classes, const chert_cell_grid*
                            (double*)a.tV, (double*)a.tA, (int32_t*)a.tS, s);
       }
       if (w.mspm)
-        CHERT_LAUNCH("k_cell_relax", k_cell_relax<true>, dim3(grelax), dim3(64 * wpb), lds, s,
-                     a, r + q);
+        CHERT_LAUNCH("k_cell_relax", (k_cell_relax<true, false>), dim3(grelax), dim3(64 * wpb),
+                     lds, s, a, r + q);
+      else if (P.dim == 3)
+        CHERT_LAUNCH("k_block_relax", (k_cell_relax<false, true>), dim3(grelax), dim3(64 * wpb),
+                     lds, s, a, r + q);
       else
-        CHERT_LAUNCH("k_cell_relax", k_cell_relax<false>, dim3(grelax), dim3(64 * wpb), lds, s,
-                     a, r + q);
+        CHERT_LAUNCH("k_cell_relax", (k_cell_relax<false, false>), dim3(grelax), dim3(64 * wpb),
+                     lds, s, a, r + q);
     }
     r += nb;
     int32_t cnt = 0;
@@ -986,11 +1243,14 @@ int trace_cells_impl(const CellSrc& w, int64_t n_classes, const chert_cell_grid*
       CHERT_LAUNCH("k_cell_zero", k_cell_zero, dim3(1), dim3(1), 0, s, a.alive);
       for (int q = 0; q < 8; ++q, ++Lv)
         if (w.mspm)
-          CHERT_LAUNCH("k_cell_level", k_cell_level<true>, dim3(gx, (unsigned)P.n_prob),
+          CHERT_LAUNCH("k_cell_level", (k_cell_level<true, false>), dim3(gx, (unsigned)P.n_prob),
                        dim3(256), 0, s, a, Lv);
+        else if (P.dim == 3)
+          CHERT_LAUNCH("k_block_level", (k_cell_level<false, true>),
+                       dim3(gx, (unsigned)P.n_prob), dim3(256), 0, s, a, Lv);
         else
-          CHERT_LAUNCH("k_cell_level", k_cell_level<false>, dim3(gx, (unsigned)P.n_prob),
-                       dim3(256), 0, s, a, Lv);
+          CHERT_LAUNCH("k_cell_level", (k_cell_level<false, false>),
+                       dim3(gx, (unsigned)P.n_prob), dim3(256), 0, s, a, Lv);
       int32_t alive = 0;
       e = hipMemcpyAsync(&alive, a.alive, sizeof(int32_t), hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1031,9 +1291,10 @@ extern "C" size_t chert_trace_cells_workspace_bytes(const chert_cache_desc* d,
                                                     int64_t n_classes,
                                                     const chert_cell_grid* g, int32_t n_src,
                                                     const chert_trace_opts* o) {
+  if (!g) return 0;
   CellSrc w;
   w.d = d;
-  return cell_workspace(w, n_classes, g, n_src, o);
+  return cell_workspace(w, n_classes, geo_of(g), n_src, o);
 }
 
 extern "C" int chert_trace_cells(const chert_cache_desc* d, const void* cache_dev,
@@ -1042,12 +1303,38 @@ extern "C" int chert_trace_cells(const chert_cache_desc* d, const void* cache_de
                                  const chert_trace_opts* o, double* tau_r_dev, double* tau_i_dev,
                                  double* tstar_dev, int32_t* pred_p_dev, int32_t* pred_a_dev,
                                  void* workspace_dev, size_t workspace_bytes, void* stream) {
+  if (!g) return fail(CHERT_ERR_INVALID_ARG, "null grid");
   CellSrc w;
   w.d = d;
   w.cache_dev = cache_dev;
-  return trace_cells_impl(w, n_classes, g, mode, src_nodes_host, n_src, o, tau_r_dev, tau_i_dev,
-                          tstar_dev, pred_p_dev, pred_a_dev, workspace_dev, workspace_bytes,
-                          stream);
+  return trace_cells_impl(w, n_classes, geo_of(g), mode, src_nodes_host, n_src, o, tau_r_dev,
+                          tau_i_dev, tstar_dev, pred_p_dev, pred_a_dev, workspace_dev,
+                          workspace_bytes, stream);
+}
+
+extern "C" size_t chert_trace_blocks_workspace_bytes(const chert_cache_desc* d,
+                                                     int64_t n_classes,
+                                                     const chert_block_grid* g, int32_t n_src,
+                                                     const chert_trace_opts* o) {
+  if (!g) return 0;
+  CellSrc w;
+  w.d = d;
+  return cell_workspace(w, n_classes, geo_of(g), n_src, o);
+}
+
+extern "C" int chert_trace_blocks(const chert_cache_desc* d, const void* cache_dev,
+                                  int64_t n_classes, const chert_block_grid* g, int32_t mode,
+                                  const int64_t* src_nodes_host, int32_t n_src,
+                                  const chert_trace_opts* o, double* tau_r_dev, double* tau_i_dev,
+                                  double* tstar_dev, int32_t* pred_p_dev, int32_t* pred_a_dev,
+                                  void* workspace_dev, size_t workspace_bytes, void* stream) {
+  if (!g) return fail(CHERT_ERR_INVALID_ARG, "null grid");
+  CellSrc w;
+  w.d = d;
+  w.cache_dev = cache_dev;
+  return trace_cells_impl(w, n_classes, geo_of(g), mode, src_nodes_host, n_src, o, tau_r_dev,
+                          tau_i_dev, tstar_dev, pred_p_dev, pred_a_dev, workspace_dev,
+                          workspace_bytes, stream);
 }
 
 extern "C" size_t chert_trace_mspm_workspace_bytes(int64_t n_classes, const chert_cell_grid* g,
@@ -1057,7 +1344,8 @@ extern "C" size_t chert_trace_mspm_workspace_bytes(int64_t n_classes, const cher
   w.kernel = CHERT_KERNEL_MEV;
   w.n_sweep = 8;
   w.classes_dev = (const chert_class*)1;  // not dereferenced by the size query
-  return cell_workspace(w, n_classes, g, n_src, o);
+  if (!g) return 0;
+  return cell_workspace(w, n_classes, geo_of(g), n_src, o);
 }
 
 extern "C" int chert_trace_mspm(const chert_class* classes_dev, int64_t n_classes,
@@ -1071,7 +1359,8 @@ extern "C" int chert_trace_mspm(const chert_class* classes_dev, int64_t n_classe
   w.classes_dev = classes_dev;
   w.kernel = kernel;
   w.n_sweep = n_sweep;
-  return trace_cells_impl(w, n_classes, g, mode, src_nodes_host, n_src, o, tau_r_dev, tau_i_dev,
-                          tstar_dev, pred_p_dev, pred_a_dev, workspace_dev, workspace_bytes,
-                          stream);
+  if (!g) return fail(CHERT_ERR_INVALID_ARG, "null grid");
+  return trace_cells_impl(w, n_classes, geo_of(g), mode, src_nodes_host, n_src, o, tau_r_dev,
+                          tau_i_dev, tstar_dev, pred_p_dev, pred_a_dev, workspace_dev,
+                          workspace_bytes, stream);
 }

@@ -95,6 +95,29 @@ def trace_cells(cache, desc, K, ncx, ncz, cn, hx, hz, class_id_np, mode, sources
     return {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
 
 
+def trace_blocks(cache, desc, K, ncx, ncy, ncz, cn, hx, hy, hz, class_id_np, mode, sources,
+                 outputs=C.OUT_ALL, bucket_width=0.0, max_rounds=0, stats=None):
+    cid = torch.from_numpy(np.ascontiguousarray(class_id_np, dtype=np.int32).reshape(-1)).to(DEV)
+    g = C.make_block_grid(ncx, ncy, ncz, cn, hx, hy, hz, cid)
+    o = C.trace_opts(outputs, bucket_width=bucket_width, max_rounds=max_rounds, stats=stats)
+    n = (ncx * cn + 1) * (ncy * cn + 1) * (ncz * cn + 1)
+    S = len(sources)
+    out = {
+        "tauR": torch.empty((S, n), dtype=torch.float64, device=DEV) if outputs & C.OUT_TAU_R else None,
+        "tauI": torch.empty((S, n), dtype=torch.float64, device=DEV) if outputs & C.OUT_TAU_I else None,
+        "tstar": torch.empty((S, n), dtype=torch.float64, device=DEV) if outputs & C.OUT_TSTAR else None,
+        "predP": torch.empty((S, n), dtype=torch.int32, device=DEV) if outputs & C.OUT_PRED_P else None,
+        "predA": torch.empty((S, n), dtype=torch.int32, device=DEV) if outputs & C.OUT_PRED_A else None,
+    }
+    wsb = C.chert_trace_blocks_workspace_bytes(desc, K, g, S, o)
+    assert wsb > 0, C.chert_last_error()
+    ws = torch.empty(wsb, dtype=torch.uint8, device=DEV)
+    C.chert_trace_blocks(desc, cache, K, g, mode, sources, o, out["tauR"], out["tauI"],
+                         out["tstar"], out["predP"], out["predA"], ws)
+    torch.cuda.synchronize()
+    return {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+
+
 def trace_mspm(classes_np, ncx, ncz, cn, hx, hz, class_id_np, mode, sources, outputs=C.OUT_ALL,
                bucket_width=0.0, kernel=C.KERNEL_MEV, n_sweep=1440, stats=None):
     cls = classes_from_arrays(classes_np)

@@ -354,7 +354,7 @@ def test_abi_struct_layouts_match_header(tmp_path):
                "chert_cache_layout": C.CacheLayout, "chert_cache_stats": C.CacheStats,
                "chert_grid": C.Grid, "chert_trace_job": C.TraceJob,
                "chert_trace_stats": C.TraceStats, "chert_trace_opts": C.TraceOpts,
-               "chert_cell_grid": C.CellGrid}
+               "chert_cell_grid": C.CellGrid, "chert_block_grid": C.BlockGrid}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "chert.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -395,3 +395,24 @@ def test_cell_network_validation():
     assert C.chert_trace_cells_workspace_bytes(d, 3, g(), 1, C.trace_opts(C.OUT_TSTAR)) == 0
     assert C.chert_trace_cells_workspace_bytes(
         C.cache_desc(n_dirs=72, modes=(2,), sampling=C.SAMPLE_SLOWNESS), 3, g(), 1, o) > 0
+
+
+def test_block_network_validation():
+    """Host checks of the block-network trace (no device call): workspace
+    bytes for valid 3D networks with a 3D cache, 0 for a 2D cache, block_n
+    outside 1..3, empty or unspaced grids and a missing class map."""
+    d = C.cache_desc(n_dirs=500, modes=(0, 1), dim=3)
+    o = C.trace_opts(C.OUT_ALL)
+    fake = 0x1000  # never dereferenced by the size query
+
+    def g(ncx=6, ncy=5, ncz=4, cn=3, hx=10.0, hy=10.0, hz=10.0, cls=fake):
+        return C.BlockGrid(ncx, ncy, ncz, cn, hx, hy, hz, cls)
+
+    b1 = C.chert_trace_blocks_workspace_bytes(d, 3, g(), 1, o)
+    b4 = C.chert_trace_blocks_workspace_bytes(d, 3, g(), 4, o)
+    assert 0 < b1 < b4
+    for cn in (1, 2):
+        assert C.chert_trace_blocks_workspace_bytes(d, 3, g(cn=cn), 1, o) > 0
+    for bad in (g(cn=0), g(cn=4), g(ncy=0), g(hy=0.0), g(hz=float("inf")), g(cls=None)):
+        assert C.chert_trace_blocks_workspace_bytes(d, 3, bad, 1, o) == 0
+    assert C.chert_trace_blocks_workspace_bytes(C.cache_desc(n_dirs=360), 3, g(), 1, o) == 0

@@ -363,3 +363,63 @@ def config5(nx=201, ny=201, nz=101, h=10.0, seed=None, n_interfaces=5, radius=3,
     src = [ix + nx * (iy + ny * iz) for ix, iy, iz in sources]
     return Model3D(f"config5_3d_layered_{nx}x{ny}x{nz}", nx, ny, nz, h, layers, cid, src,
                    (QP, QSV), radius)
+
+
+@dataclass
+class BlockModel3D:
+    name: str
+    ncx: int
+    ncy: int
+    ncz: int
+    block_n: int
+    h: float                      # lattice spacing (block edge / block_n)
+    layers: List[Layer]
+    class_id: np.ndarray          # int32 [NZ, NY, NX] over the lattice
+    sources: List[int]            # lattice nodes ix + NX (iy + NY iz)
+    receivers: List[int]
+    modes: tuple
+    n_dirs: int = 41253
+
+    @property
+    def lattice(self):
+        n = self.block_n
+        return self.ncx * n + 1, self.ncy * n + 1, self.ncz * n + 1
+
+
+def blocks_3d(ncx=18, ncy=18, ncz=4, block_n=3, block=160.0, seed=None, n_layers=4,
+              tilt_deg=25.0, n_rcv_side=19):
+    """Compact 3D TTI on the block network: 18 x 18 x 4 blocks of 160 m
+    (2880 m x 2880 m laterally, 640 m deep, 1296 blocks), block_n lattice
+    intervals per block edge; n_layers layers with the layered model's
+    parameter ranges, every layer tilted tilt_deg with a seeded azimuth;
+    interfaces at equal depths with seeded two-way sine undulations
+    (amplitude <= 40 m); one surface source at the centre and a
+    n_rcv_side x n_rcv_side surface receiver grid on the block corners."""
+    rng = np.random.default_rng(seed_for(6) if seed is None else seed)
+    layers = []
+    for _ in range(n_layers):
+        L = _layer_params(rng)
+        L.tilt = math.radians(tilt_deg)
+        L.azimuth = math.radians(rng.uniform(0.0, 360.0))
+        layers.append(L)
+    h = block / block_n
+    NX, NY, NZ = ncx * block_n + 1, ncy * block_n + 1, ncz * block_n + 1
+    x = np.arange(NX) * h
+    y = np.arange(NY) * h
+    z = np.arange(NZ) * h
+    X, Y = np.meshgrid(x, y)                      # [NY, NX]
+    depth = (NZ - 1) * h
+    cid = np.zeros((NZ, NY, NX), np.int32)
+    for k in range(1, n_layers):
+        amp = rng.uniform(0.0, 40.0)
+        lx, ly = rng.uniform(800.0, 3000.0, 2)
+        px, py = rng.uniform(0.0, 2 * math.pi, 2)
+        zi = k * depth / n_layers + amp * np.sin(2 * math.pi * X / lx + px) * np.cos(
+            2 * math.pi * Y / ly + py)
+        cid += (z[:, None, None] > zi[None, :, :]).astype(np.int32)
+    src = [(NX // 2 // block_n) * block_n + NX * ((NY // 2 // block_n) * block_n)]
+    step_x = max(1, ncx // (n_rcv_side - 1)) * block_n
+    step_y = max(1, ncy // (n_rcv_side - 1)) * block_n
+    rcv = [ix + NX * iy for iy in range(0, NY, step_y) for ix in range(0, NX, step_x)]
+    return BlockModel3D(f"blocks3d_{ncx}x{ncy}x{ncz}_n{block_n}", ncx, ncy, ncz, block_n, h,
+                        layers, cid, src, rcv, (QP, QSV))
