@@ -19,7 +19,7 @@
 //
 // Predecessors and t*: level-synchronous BFS over tight segments
 // (tau_i + w_ij == tau_j) from the source, one launch per level, threads
-// over (node, cell, boundary slot) triples: pred_j = the tight neighbour one
+// over (node, boundary slot) pairs: pred_j = the tight neighbour one
 // level up with the smallest node
 // index (the smallest (hop, index) among all tight neighbours), t*_j =
 // t*_pred + the attenuation weight of that segment, each parent's value
@@ -45,6 +45,7 @@ constexpr int kCellMaxN = 16;  // 4 cn boundary nodes <= 64 lanes
 constexpr int kBlockMaxN = 3;  // (cn + 1)^3 - (cn - 1)^3 face nodes <= 64 lanes
 constexpr int kCellWaves = 4;  // waves per workgroup
 constexpr int kCellThreads = 64 * kCellWaves;
+constexpr int kRelaxGrid = 4096;  // most workgroups of a relax launch
 constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -143,6 +144,7 @@ struct CellArgs {
   int32_t* list;               // [P C] selected (problem, cell) items
   int32_t* count;              // [2] (round parity)
   unsigned long long* stats;   // visits, pair relaxations, passes, MSPM corner jobs
+  unsigned long long* part;    // [kRelaxGrid][3] per-workgroup visits, pairs, passes
   const double* wmin;          // [2]
   double bucket;               // ordering width in units of wmin (0: none)
   // level phase
@@ -229,6 +231,13 @@ __device__ __forceinline__ double mspm_w(const CellArgs& a, int f, const Rows4& 
 
 // Weight of segment i -> j of cell c (field f): the class-pair table of a
 // cached network, or MSPM's reconstruction from the class table.
+// cached network: weight of a segment of offset index off from class ki to
+// class kj (field f)
+__device__ __forceinline__ double pair_w(const CellArgs& a, int f, int ki, int kj, int off) {
+  const int64_t no = a.n_off;
+  return a.W[((int64_t)f * a.K * a.K + (int64_t)ki * a.K + kj) * no + off];
+}
+
 template <bool MSPM, bool D3>
 __device__ __forceinline__ double seg_weight(const CellArgs& a, int f, int c, int64_t i,
                                              int64_t j) {
@@ -237,9 +246,7 @@ __device__ __forceinline__ double seg_weight(const CellArgs& a, int f, int c, in
     int ix, iy, iz, jx, jy, jz;
     node_xyz<D3>(a, i, ix, iy, iz);
     node_xyz<D3>(a, j, jx, jy, jz);
-    const int64_t no = a.n_off;
-    const int off = off_of<D3>(a, jx - ix, jy - iy, jz - iz);
-    return a.W[(int64_t)f * a.K * a.K * no + ((int64_t)a.cls[i] * a.K + a.cls[j]) * no + off];
+    return pair_w(a, f, a.cls[i], a.cls[j], off_of<D3>(a, jx - ix, jy - iy, jz - iz));
   } else {
     static_assert(!D3, "MSPM runs on the 2D cell network");
     const int ix = (int)(i % a.NX), iz = (int)(i / a.NX), jx = (int)(j % a.NX),
@@ -264,17 +271,19 @@ __device__ __forceinline__ int common_cell(const CellArgs& a, int64_t i, int64_t
   return cs[0];
 }
 
-// lattice node -> (x, y, z) and back (2D: y = 0)
+// lattice node -> (x, y, z) and back (2D: y = 0); lattices hold fewer than
+// 2^31 points, so 32-bit division suffices
 template <bool D3>
 __device__ __forceinline__ void node_xyz(const CellArgs& a, int64_t u, int& x, int& y, int& z) {
-  x = (int)(u % a.NX);
-  const int64_t r = u / a.NX;
+  const int v = (int)u;
+  x = v % a.NX;
+  const int r = v / a.NX;
   if constexpr (D3) {
-    y = (int)(r % a.NY);
-    z = (int)(r / a.NY);
+    y = r % a.NY;
+    z = r / a.NY;
   } else {
     y = 0;
-    z = (int)r;
+    z = r;
   }
 }
 __device__ __forceinline__ int64_t node_at(const CellArgs& a, int x, int y, int z) {
@@ -359,6 +368,10 @@ __global__ void k_cell_fill(CellArgs a) {
     if (pr) pr[i] = -1;
     if (ts) ts[i] = INFINITY;
   }
+  if (p == 0)
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < 3 * kRelaxGrid;
+         q += gridDim.x * blockDim.x)
+      a.part[q] = 0ull;
   int32_t* act = a.active + (int64_t)p * a.C;
   unsigned long long* ky = a.key + (int64_t)p * a.C;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.C;
@@ -418,15 +431,36 @@ __global__ void k_cell_select(CellArgs a, int r) {
        base += (int64_t)gridDim.x * blockDim.x) {
     const int64_t t = base + threadIdx.x;
     bool take = false;
+    int p = -1;
+    unsigned long long defer = kInfBits;
     if (t < total && a.active[t]) {
       take = true;
       if (a.bucket > 0.0) {
-        const int p = (int)(t / a.C);
+        p = (int)(t / a.C);
         const int f = a.field_of[p / a.n_src];
         const unsigned long long k = a.key[t];
         const double lim = __longlong_as_double((long long)mk[p]) + a.bucket * a.wmin[f];
         take = __longlong_as_double((long long)k) <= lim;
-        if (!take) atomicMin(&mk_next[p], k);
+        if (!take) defer = k;
+      }
+    }
+    if (a.bucket > 0.0) {
+      // deferred keys bid for the next round's minimum; when the wave's
+      // deferred cells share one problem it reduces first and bids once
+      // (atomics on one address serialise)
+      const unsigned long long dm = __ballot(defer != kInfBits);
+      if (dm) {
+        const int p0 = __shfl(p, __ffsll((long long)dm) - 1);
+        if (__ballot(defer != kInfBits && p != p0) == 0) {
+          unsigned long long m = defer;
+          for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long m2 = __shfl_xor(m, o);
+            m = m2 < m ? m2 : m;
+          }
+          if (lane == 0) atomicMin(&mk_next[p0], m);
+        } else if (defer != kInfBits) {
+          atomicMin(&mk_next[p], defer);
+        }
       }
     }
     const unsigned long long m = __ballot(take);
@@ -462,6 +496,7 @@ __global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) 
   // dynamic LDS: [the class-pair table, when it fits][waves][ns][ns]
   extern __shared__ double s_w[];
   __shared__ unsigned long long s_wake[kCellWaves][NNB];  // per neighbour cell
+  __shared__ unsigned long long s_part[kCellWaves][3];
   const int lane = threadIdx.x & 63;
   const int wib = threadIdx.x >> 6;
   const int wpb = blockDim.x >> 6;
@@ -581,6 +616,7 @@ __global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) 
       }
     }
     wave_sync_lds();
+    unsigned long long woke = kInfBits;
     if (lane < NNB) {
       const unsigned long long v = s_wake[wib][lane];
       const int d = lane < kSelf ? lane : lane + 1;
@@ -593,31 +629,63 @@ __global__ void __launch_bounds__(kCellThreads) k_cell_relax(CellArgs a, int r) 
         const int64_t e = (int64_t)p * a.C + nx + (int64_t)a.ncx * (ny + (int64_t)a.ncy * nz);
         atomicMin(&a.key[e], v);
         a.active[e] = 1;
-        if (a.bucket > 0.0) atomicMin(&a.minkey[(int64_t)((r + 1) % 3) * a.n_prob + p], v);
+        woke = v;
       }
+    }
+    // the next round's smallest key of the problem: one atomic per visit
+    // (atomics on one address serialise, so the wave reduces first)
+    if (a.bucket > 0.0) {
+      for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long w2 = __shfl_xor(woke, o);
+        woke = w2 < woke ? w2 : woke;
+      }
+      if (lane == 0 && woke != kInfBits)
+        atomicMin(&a.minkey[(int64_t)((r + 1) % 3) * a.n_prob + p], woke);
     }
     wave_sync_lds();
   }
-  if (lane == 0 && visits) {
-    atomicAdd(&a.stats[0], visits);
-    atomicAdd(&a.stats[1], pairs);
-    atomicAdd(&a.stats[2], passes_all);
+  // statistics: per-workgroup partial sums in plain stores (no atomics on a
+  // shared address), summed by the host
+  if (lane == 0) {
+    s_part[wib][0] = visits;
+    s_part[wib][1] = pairs;
+    s_part[wib][2] = passes_all;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && blockIdx.x < kRelaxGrid) {
+    unsigned long long v0 = 0, v1 = 0, v2 = 0;
+    for (int w = 0; w < wpb; ++w) {
+      v0 += s_part[w][0];
+      v1 += s_part[w][1];
+      v2 += s_part[w][2];
+    }
+    if (v0) {
+      unsigned long long* pp = a.part + 3 * (int64_t)blockIdx.x;
+      pp[0] += v0;
+      pp[1] += v1;
+      pp[2] += v2;
+    }
   }
 }
 
 // Predecessors and t*, level L of the BFS over tight segments, one launch
-// per level, grid (x, problem).  Step 1 (level L): every thread takes
-// (node j of the level, one of j's cells, one boundary slot v of that cell)
-// triples: a tight v one level up (tau_v + w(v->j) == tau_j) bids for pred_j
+// per level, grid (x, problem).  Step 1 (level L): every thread takes a
+// (node j of the level, boundary slot) pair and visits the slot's point v
+// in each of j's cells: a tight v one level up (tau_v + w(v->j) == tau_j)
+// bids for pred_j
 // with an atomicMin on its index; a v not yet reached with
 // tau_j + w(j->v) == tau_v joins level L + 1 (one winner per node through a
 // compare-and-swap on its hop).  Step 2 (level L - 1, whose bids were final
 // when the previous launch ended): pred_j and t*_j = t*_pred + the
 // attenuation weight of that segment (the parent's value final one level
 // earlier).  Level bounds rotate through three slots per problem.
+constexpr int kLvlThreads = 256;
+constexpr int kLvlBuf = 4096;  // appends staged per workgroup (16 KiB of LDS)
 template <bool MSPM, bool D3>
-__global__ void __launch_bounds__(256) k_cell_level(CellArgs a, int L) {
+__global__ void __launch_bounds__(kLvlThreads) k_cell_level(CellArgs a, int L) {
   static_assert(!(MSPM && D3), "MSPM runs on the 2D cell network");
+  __shared__ int32_t s_buf[kLvlBuf];
+  __shared__ int s_n, s_base, s_any;
   const int p = blockIdx.y;
   const int fi = p / a.n_src, s = p - fi * a.n_src;
   if (!((a.tree_mask >> fi) & 1)) return;
@@ -632,7 +700,7 @@ __global__ void __launch_bounds__(256) k_cell_level(CellArgs a, int L) {
   int32_t* cnt = a.cnt + (L % 3) * P + p;
   const int ns = D3 ? a.ns : 4 * a.cn;
   constexpr int kCells = D3 ? 8 : 4;  // cells (blocks) a node can lie on
-  const int per = kCells * ns;        // (cell, slot) triples per node
+  const int cn = a.cn;
   const int f = a.field_of[fi];
   const double* tau = a.tau[fi] + (int64_t)s * a.n;
   int32_t* hop = a.hop + (int64_t)p * a.n;
@@ -642,30 +710,112 @@ __global__ void __launch_bounds__(256) k_cell_level(CellArgs a, int L) {
   double* ts = (a.tstar && f == 0) ? a.tstar + (int64_t)s * a.n : nullptr;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
-  int added = 0;
-  const int64_t work = (int64_t)(end - start) * per;
-  for (int64_t t = tid; t < work; t += nthr) {
-    const int64_t j = bfs[start + (int)(t / per)];
-    const int q = (int)((t / ns) & (kCells - 1)), sl = (int)(t % ns);
-    int cs[kCells];
-    const int nc = node_cells<D3>(a, j, cs);
-    if (q >= nc) continue;
-    int lx, ly, lz, x0, y0, z0;
-    slot_pos<D3>(a, sl, lx, ly, lz);
-    cell_origin<D3>(a, cs[q], x0, y0, z0);
-    const int64_t v = node_at(a, x0 + lx, y0 + ly, z0 + lz);
-    if (v == j) continue;
-    const double tj = tau[j], tv = tau[v];
-    const int hv = hop[v];
-    if (L > 0 && hv == L - 1) {  // v -> j tight?
-      if (tv + seg_weight<MSPM, D3>(a, f, cs[q], v, j) == tj) atomicMin(&bid[j], (int)v);
-    }
-    if (hv == -1 && tv < INFINITY) {  // j -> v tight?
-      if (tj + seg_weight<MSPM, D3>(a, f, cs[q], j, v) == tv &&
-          atomicCAS(&hop[v], -1, L + 1) == -1) {
-        bfs[end + atomicAdd(cnt, 1)] = (int32_t)v;
-        ++added;
+  // one thread per (node of the level, boundary slot), looping over the
+  // node's cells; a slot point that also lies on an earlier cell of the
+  // node was handled there by the thread of its slot in that cell (it is a
+  // face point of every cell whose closed box holds it), so each neighbour
+  // is examined once.  Appends to the next level are staged in LDS and
+  // reserved in the global list once per workgroup flush (device-scope
+  // atomics on one address serialise across the chip).
+  if (threadIdx.x == 0) {
+    s_n = 0;
+    s_any = 0;
+  }
+  __syncthreads();
+  const int64_t work = (int64_t)(end - start) * ns;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < work; base += nthr) {
+    const int64_t t = base + threadIdx.x;
+    const bool valid = t < work;
+    int64_t j = 0;
+    int lx = 0, ly = 0, lz = 0, jx = 0, jy = 0, jz = 0, kj = 0;
+    // the node's cells per axis: origins o?[0..n?-1] (two on a cell
+    // boundary plane, else one)
+    int nxa = 0, nya = 1, nza = 0, ox[2] = {0, 0}, oy[2] = {0, 0}, oz[2] = {0, 0};
+    double tj = 0.0;
+    if (valid) {
+      j = bfs[start + (int)(t / ns)];
+      slot_pos<D3>(a, (int)(t % ns), lx, ly, lz);
+      node_xyz<D3>(a, j, jx, jy, jz);
+      tj = tau[j];
+      kj = MSPM ? 0 : a.cls[j];
+      int c3[2];
+      nxa = cells_along(jx, cn, a.ncx, c3);
+      ox[0] = c3[0] * cn;
+      ox[1] = c3[nxa - 1] * cn;
+      if constexpr (D3) {
+        nya = cells_along(jy, cn, a.ncy, c3);
+        oy[0] = c3[0] * cn;
+        oy[1] = c3[nya - 1] * cn;
       }
+      nza = cells_along(jz, cn, a.ncz, c3);
+      oz[0] = c3[0] * cn;
+      oz[1] = c3[nza - 1] * cn;
+    }
+    // three passes over the node's cells so that each pass's memory
+    // operations are independent and overlap: (1) tightness tests (loads
+    // only), (2) the bids and the claims of unreached nodes (atomics, issued
+    // back to back), (3) appends of the claimed nodes.  A slot point that
+    // also lies on the node's other cell along an axis (local coordinate 0
+    // in the upper cell) is examined in the lower cell only, so each
+    // neighbour is examined once.
+    int32_t upv[kCells], dnv[kCells];
+#pragma unroll
+    for (int q = 0; q < kCells; ++q) {
+      const int ia = D3 ? (q >> 2) : (q >> 1), ib = D3 ? ((q >> 1) & 1) : 0, ic = q & 1;
+      upv[q] = -1;
+      dnv[q] = -1;
+      const bool have = ia < nxa && ib < nya && ic < nza;
+      const bool dup = (ia == 1 && lx == 0) || (ib == 1 && ly == 0) || (ic == 1 && lz == 0);
+      if (have && !dup) {
+        const int vx = ox[ia] + lx, vy = oy[ib] + ly, vz = oz[ic] + lz;
+        const int64_t v = node_at(a, vx, vy, vz);
+        if (v != j) {
+          const double tv = tau[v];
+          const int hv = hop[v];
+          const bool up = L > 0 && hv == L - 1, down = hv == -1 && tv < INFINITY;
+          if (up || down) {
+            const int kv = MSPM ? 0 : a.cls[v];
+            // MSPM reads the cell (2D): cell index of (ia, ic)
+            const int c = MSPM ? ox[ia] / cn + a.ncx * (oz[ic] / cn) : 0;
+            if (up) {  // v -> j tight?
+              const double w =
+                  MSPM ? seg_weight<MSPM, D3>(a, f, c, v, j)
+                       : pair_w(a, f, kv, kj, off_of<D3>(a, jx - vx, jy - vy, jz - vz));
+              if (tv + w == tj) upv[q] = (int32_t)v;
+            }
+            if (down) {  // j -> v tight?
+              const double w =
+                  MSPM ? seg_weight<MSPM, D3>(a, f, c, j, v)
+                       : pair_w(a, f, kj, kv, off_of<D3>(a, vx - jx, vy - jy, vz - jz));
+              if (tj + w == tv) dnv[q] = (int32_t)v;
+            }
+          }
+        }
+      }
+    }
+    bool won[kCells];
+#pragma unroll
+    for (int q = 0; q < kCells; ++q) {
+      if (upv[q] >= 0) atomicMin(&bid[j], upv[q]);
+      won[q] = dnv[q] >= 0 && atomicCAS(&hop[dnv[q]], -1, L + 1) == -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kCells; ++q)
+      if (won[q]) s_buf[atomicAdd(&s_n, 1)] = dnv[q];  // LDS atomic
+    // flush when another pass could overflow the buffer (workgroup-uniform)
+    __syncthreads();
+    const int n_st = s_n;
+    __syncthreads();  // every thread has read the count before the next pass adds to it
+    if (n_st > kLvlBuf - kLvlThreads * kCells || (n_st > 0 && base + nthr >= work)) {
+      if (threadIdx.x == 0) {
+        s_base = atomicAdd(cnt, n_st);
+        s_any = 1;
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < n_st; i += blockDim.x) bfs[end + s_base + i] = s_buf[i];
+      __syncthreads();
+      if (threadIdx.x == 0) s_n = 0;
+      __syncthreads();
     }
   }
   if (L >= 2) {
@@ -680,26 +830,31 @@ __global__ void __launch_bounds__(256) k_cell_level(CellArgs a, int L) {
       if (ts) ts[j] = ts[b] + seg_weight<MSPM, D3>(a, 1, MSPM ? common_cell(a, b, j) : 0, b, j);
     }
   }
-  for (int o = 32; o > 0; o >>= 1) added += __shfl_xor(added, o);
-  if (__lane_id() == 0 && added) atomicAdd(a.alive, added);
+  // any append keeps the BFS going; a plain store of 1 by the workgroups
+  // that appended (the host only tests for zero)
+  if (threadIdx.x == 0 && s_any) *a.alive = 1;
 }
 
 __global__ void k_cell_zero(int32_t* x) { *x = 0; }
 
-// 3D segment columns: one wave per offset o, the Fibonacci direction with
-// the largest dot product f . u_o (IEEE operations in the order of the
-// definition, no contraction), the lowest index among equals: each lane
-// keeps its first strict maximum over a strided pass, then the wave merges
-// (larger dot first, lower index on a tie), which is the sequential rule.
-__global__ void __launch_bounds__(256) k_fib_nearest(const double* f, int N, const double* u,
-                                                     int n_off, int32_t* col) {
-  const int o = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (o >= n_off) return;
-  const int lane = threadIdx.x & 63;
+// 3D segment columns: one workgroup per offset o, the Fibonacci direction
+// with the largest dot product f . u_o (IEEE operations in the order of the
+// definition, no contraction), the lowest index among equals: each thread
+// keeps its first strict maximum over a strided pass, then the waves and
+// the workgroup merge (larger dot first, lower index on a tie), which is the
+// sequential rule.
+constexpr int kFibThreads = 1024;
+__global__ void __launch_bounds__(kFibThreads) k_fib_nearest(const double* f, int N,
+                                                             const double* u, int n_off,
+                                                             int32_t* col) {
+  __shared__ double s_d[kFibThreads / 64];
+  __shared__ int s_i[kFibThreads / 64];
+  const int o = blockIdx.x;  // grid = n_off
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double u0 = u[3 * o], u1 = u[3 * o + 1], u2 = u[3 * o + 2];
   double bd = -2.0;
   int bi = 0x7fffffff;
-  for (int i = lane; i < N; i += 64) {
+  for (int i = threadIdx.x; i < N; i += kFibThreads) {
     const double d = __dadd_rn(__dadd_rn(__dmul_rn(f[3 * i], u0), __dmul_rn(f[3 * i + 1], u1)),
                                __dmul_rn(f[3 * i + 2], u2));
     if (d > bd) {
@@ -715,7 +870,19 @@ __global__ void __launch_bounds__(256) k_fib_nearest(const double* f, int N, con
       bi = oi;
     }
   }
-  if (lane == 0) col[o] = bi;
+  if (lane == 0) {
+    s_d[wv] = bd;
+    s_i[wv] = bi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kFibThreads / 64; ++w)
+      if (s_d[w] > bd || (s_d[w] == bd && s_i[w] < bi)) {
+        bd = s_d[w];
+        bi = s_i[w];
+      }
+    col[o] = bi;
+  }
 }
 
 // ---------------------------------------------------------------- plan ----
@@ -812,7 +979,7 @@ struct CellPlan {
   bool slow = false;
   size_t off_tab = 0, off_geo = 0, off_W = 0, off_best = 0, off_ctl = 0, off_src = 0,
          off_act = 0, off_key = 0, off_list = 0, off_hop = 0, off_bfs = 0, off_bid = 0,
-         off_kt = 0, off_vt = 0, off_jobs = 0, total = 0;
+         off_kt = 0, off_vt = 0, off_jobs = 0, off_part = 0, total = 0;
 };
 
 int cell_plan(const CellSrc& w, int64_t n_classes, const CellGeo& G, int32_t mode,
@@ -917,6 +1084,8 @@ int cell_plan(const CellSrc& w, int64_t n_classes, const CellGeo& G, int32_t mod
   P->off_ctl = off;  // count[2], err, alive, stats[4], wmin[2], minkey[3][P], bnd, cnt
   off += al256(256 + (size_t)3 * P->n_prob * sizeof(unsigned long long) +
                (size_t)6 * P->n_prob * sizeof(int32_t));
+  P->off_part = off;
+  off += al256((size_t)3 * kRelaxGrid * sizeof(unsigned long long));
   P->off_src = off;
   off += al256((size_t)n_src * sizeof(int64_t));
   P->off_act = off;
@@ -1062,7 +1231,7 @@ int trace_cells_impl(const CellSrc& w, int64_t n_classes, const CellGeo& G, int3
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // host buffers are locals
   if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
   if (P.dim == 3)  // the closest Fibonacci direction of every offset
-    CHERT_LAUNCH("k_fib_nearest", k_fib_nearest, dim3((unsigned)((s2 + 3) / 4)), dim3(256), 0, s,
+    CHERT_LAUNCH("k_fib_nearest", k_fib_nearest, dim3((unsigned)s2), dim3(kFibThreads), 0, s,
                  dgeo + 3 * (size_t)s2, P.N, dgeo, s2, dtab + 2 * s2);
 
   uint8_t* ctl = ws + P.off_ctl;
@@ -1089,6 +1258,7 @@ int trace_cells_impl(const CellSrc& w, int64_t n_classes, const CellGeo& G, int3
   int32_t* err = (int32_t*)(ctl + 8);
   a.alive = (int32_t*)(ctl + 12);
   a.stats = (unsigned long long*)(ctl + 16);
+  a.part = (unsigned long long*)(ws + P.off_part);
   double* wmin = (double*)(ctl + 48);
   a.wmin = wmin;
   a.minkey = (unsigned long long*)(ctl + 256);
@@ -1197,7 +1367,7 @@ int trace_cells_impl(const CellSrc& w, int64_t n_classes, const CellGeo& G, int3
   a.w_lds = 0;
   const size_t lds = (size_t)wpb * ns * ns * sizeof(double);
   const unsigned grelax =
-      (unsigned)((items + wpb - 1) / wpb > 4096 ? 4096 : (items + wpb - 1) / wpb);
+      (unsigned)((items + wpb - 1) / wpb > kRelaxGrid ? kRelaxGrid : (items + wpb - 1) / wpb);
   const unsigned gjobs = (unsigned)((4 * items + 255) / 256 > 1024 ? 1024 : (4 * items + 255) / 256);
   const int64_t gsolve = 4 * items > 16384 ? 16384 : 4 * items;
   int rounds = -1;
@@ -1236,21 +1406,23 @@ int trace_cells_impl(const CellSrc& w, int64_t n_classes, const CellGeo& G, int3
   // predecessors and t*: one launch per level, the host checking every 8
   int levels = 0;
   if (a.tree_mask) {
-    unsigned gx = (unsigned)(2048 / P.n_prob);
+    // few workgroups per problem: each reserves its staged appends with one
+    // atomic per flush
+    unsigned gx = (unsigned)(1024 / P.n_prob);
     if (gx < 1) gx = 1;
-    if (gx > 256) gx = 256;
+    if (gx > 128) gx = 128;
     for (int Lv = 0;;) {
       CHERT_LAUNCH("k_cell_zero", k_cell_zero, dim3(1), dim3(1), 0, s, a.alive);
       for (int q = 0; q < 8; ++q, ++Lv)
         if (w.mspm)
           CHERT_LAUNCH("k_cell_level", (k_cell_level<true, false>), dim3(gx, (unsigned)P.n_prob),
-                       dim3(256), 0, s, a, Lv);
+                       dim3(kLvlThreads), 0, s, a, Lv);
         else if (P.dim == 3)
           CHERT_LAUNCH("k_block_level", (k_cell_level<false, true>),
-                       dim3(gx, (unsigned)P.n_prob), dim3(256), 0, s, a, Lv);
+                       dim3(gx, (unsigned)P.n_prob), dim3(kLvlThreads), 0, s, a, Lv);
         else
           CHERT_LAUNCH("k_cell_level", (k_cell_level<false, false>),
-                       dim3(gx, (unsigned)P.n_prob), dim3(256), 0, s, a, Lv);
+                       dim3(gx, (unsigned)P.n_prob), dim3(kLvlThreads), 0, s, a, Lv);
       int32_t alive = 0;
       e = hipMemcpyAsync(&alive, a.alive, sizeof(int32_t), hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1266,9 +1438,15 @@ int trace_cells_impl(const CellSrc& w, int64_t n_classes, const CellGeo& G, int3
   }
   if (o->stats_host) {
     unsigned long long st[4] = {0, 0, 0, 0};
+    std::vector<unsigned long long> part((size_t)3 * kRelaxGrid);
     e = hipMemcpyAsync(st, a.stats, sizeof(st), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(part.data(), a.part, part.size() * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+    for (int b = 0; b < kRelaxGrid; ++b)
+      for (int i = 0; i < 3; ++i) st[i] += part[3 * (size_t)b + i];
     chert_trace_stats* ts = o->stats_host;
     memset(ts, 0, sizeof(*ts));
     ts->rounds[0] = rounds;
