@@ -20,6 +20,32 @@ constexpr int kMaxRadius3 = 4;    // 3D star radius limit
 constexpr int kMaxOffsets3 = 728; // (2R+1)^3 - 1 bound on |O_R| in 3D for R <= 4
 constexpr int kMaxFibonacci = 1 << 20;
 
+// Statistics counters sharded over kStatSlots slots of 128 bytes: device-
+// scope atomics on one address serialise across the chip (tens of ns each
+// when thousands of workgroups hit it in a launch), so a workgroup adds into
+// the slot of its index and the host reduces the slots.
+constexpr int kStatSlots = 256;
+constexpr int kStatSlotU64 = 16;  // counters per slot (128 bytes)
+constexpr size_t kStatBytes = (size_t)kStatSlots * kStatSlotU64 * sizeof(unsigned long long);
+
+__device__ __forceinline__ unsigned long long* stat_slot(unsigned long long* base) {
+  return base + (size_t)(blockIdx.x & (kStatSlots - 1)) * kStatSlotU64;
+}
+
+// out[i] = sum over slots of counter i, or the maximum for the bits set in
+// max_mask; n <= kStatSlotU64.
+inline void stats_reduce(const unsigned long long* slots, int n, uint32_t max_mask,
+                         unsigned long long* out) {
+  for (int i = 0; i < n; ++i) {
+    unsigned long long v = 0;
+    for (int q = 0; q < kStatSlots; ++q) {
+      const unsigned long long x = slots[(size_t)q * kStatSlotU64 + i];
+      v = ((max_mask >> i) & 1u) ? (x > v ? x : v) : v + x;
+    }
+    out[i] = v;
+  }
+}
+
 // Record a failure message for chert_last_error() and return the code.
 int fail(int code, const char* msg);
 

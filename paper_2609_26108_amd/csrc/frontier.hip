@@ -113,7 +113,8 @@ struct RF {
   int64_t cap;
   int32_t* counts;  // [max_iter + 2] frontier size of each iteration
   int32_t* err;
-  unsigned long long* stats;  // [0] iterations run with work, [1] edges examined
+  unsigned long long* stats;  // [kStatSlots][16] shards of: [0] iterations run with
+                              // work, [1] edges examined
   double* thr;        // [n_prob] current threshold (+inf: one bucket)
   double* thr_min;    // [n_prob] far-pile minimum (scratch of the split)
   double* wmin;       // [2] smallest positive edge weight per field
@@ -145,13 +146,15 @@ __device__ __forceinline__ int step(const JobF& J, const RF& a, int i, int o, in
 }
 
 __global__ void k_front_clear(int32_t* counts, int n_counts, int32_t* err,
-                              unsigned long long* stats) {
+                              unsigned long long* stats, int32_t* far_count) {
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n_counts; t += gridDim.x * blockDim.x)
     counts[t] = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < kStatSlots * kStatSlotU64;
+       t += gridDim.x * blockDim.x)
+    stats[t] = 0ull;
   if (blockIdx.x == 0 && threadIdx.x < 4) {
     if (threadIdx.x == 0) *err = 0;
-    stats[threadIdx.x] = 0ull;
-    reinterpret_cast<int32_t*>(stats + 8)[threadIdx.x] = 0;  // far-pile counts
+    far_count[threadIdx.x] = 0;  // far-pile counts
   }
 }
 
@@ -319,7 +322,7 @@ __global__ void __launch_bounds__(kFrontierThreads) k_front_relax(RF a, int it, 
       append64(later, out, far, &a.far_count[epoch & 1]);
     }
   }
-  if (lane == 0 && raw) atomicAdd(&a.stats[1], (unsigned long long)raw);
+  if (lane == 0 && raw) atomicAdd(&stat_slot(a.stats)[1], (unsigned long long)raw);
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.stats[0], 1ull);
 }
 
@@ -452,6 +455,7 @@ struct PlanF {
   int dim = 0, R = 0, n_off = 0, n_prob = 0, max_iter = 0;
   int64_t cap = 0;
   bool tiles = false;  // 3D traveltimes on tiles (tile3d.hip) instead of the frontier
+  size_t off_stats = 0;
   size_t off_star = 0, off_lcol = 0, off_jobs = 0, off_probs = 0, off_counts = 0, off_err = 0,
          off_lists = 0, off_far = 0, off_thr = 0, off_lut = 0, off_tiles = 0, total = 0;
   std::vector<size_t> off_W, off_stamp;  // per job, per problem (near and far stamps)
@@ -550,6 +554,8 @@ static int make_plan_f(const chert_trace_job* jobs, int n_jobs, const chert_trac
   off += align256((size_t)kLutSide * kLutSide * kLutSide * sizeof(int16_t));
   P->off_err = off;
   off += 256;
+  P->off_stats = off;
+  off += align256(kStatBytes);
   P->off_W.clear();
   for (int j = 0; j < n_jobs; ++j) {
     P->off_W.push_back(off);
@@ -724,7 +730,7 @@ int trace_batch_frontier(const chert_trace_job* jobs, int n_jobs, const chert_tr
   a.cap = P.cap;
   a.counts = (int32_t*)(ws + P.off_counts);
   a.err = (int32_t*)(ws + P.off_err);
-  a.stats = (unsigned long long*)(ws + P.off_err + 64);
+  a.stats = (unsigned long long*)(ws + P.off_stats);
   a.far_count = (int32_t*)(ws + P.off_err + 128);
   a.thr = (double*)(ws + P.off_thr);
   a.thr_min = a.thr + P.n_prob;
@@ -735,7 +741,7 @@ int trace_batch_frontier(const chert_trace_job* jobs, int n_jobs, const chert_tr
   a.lut = (const int16_t*)(ws + P.off_lut);
   a.R = P.R;
   CHERT_LAUNCH("k_front_clear", k_front_clear, dim3(64), dim3(256), 0, s, a.counts,
-               P.max_iter + 2, a.err, a.stats);
+               P.max_iter + 2, a.err, a.stats, a.far_count);
   // class ids checked before any output is written
   {
     bool any_map = false;
@@ -848,10 +854,12 @@ int trace_batch_frontier(const chert_trace_job* jobs, int n_jobs, const chert_tr
   }
   int32_t herr = 0;
   unsigned long long hstats[2] = {0, 0};
+  std::vector<unsigned long long> slots((size_t)kStatSlots * kStatSlotU64);
   e = hipMemcpyAsync(&herr, a.err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(hstats, a.stats, sizeof(hstats), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(slots.data(), a.stats, kStatBytes, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+  stats_reduce(slots.data(), 2, 0u, hstats);
   if (o->stats_host) {
     chert_trace_stats* st = o->stats_host;
     *st = chert_trace_stats{};

@@ -121,7 +121,8 @@ __global__ void k_tile3_clear(int32_t* flags, int64_t n_flags, int32_t* counter,
   for (int64_t t = tid; t < n_flags; t += (int64_t)gridDim.x * blockDim.x) flags[t] = 0;
   for (int64_t t = tid; t < n_counter; t += (int64_t)gridDim.x * blockDim.x) counter[t] = 0;
   if (tid == 0) *err = 0;
-  if (tid < 2) stats[tid] = 0ull;
+  for (int64_t t = tid; t < kStatSlots * kStatSlotU64; t += (int64_t)gridDim.x * blockDim.x)
+    stats[t] = 0ull;
 }
 
 // activate the source tile of every problem
@@ -316,12 +317,14 @@ __device__ void visit3(const T3Args& a, int round, int T) {
   if (mask) atomicOr(&s_mask, mask);
   __syncthreads();
   if (threadIdx.x == 0) {
-    atomicAdd(&a.stats[0], 1ull);
-    atomicAdd(&a.stats[1], (unsigned long long)(raw + (long long)s_npull * n_off));
+    unsigned long long* st = stat_slot(a.stats);
+    atomicAdd(&st[0], 1ull);
+    atomicAdd(&st[1], (unsigned long long)(raw + (long long)s_npull * n_off));
     const int m = s_mask;
     if (m) {
       int32_t* fout = a.flags + (int64_t)((round + 1) & 1) * a.n_tiles;
       int32_t* lout = a.list + (int64_t)((round + 1) & 1) * a.n_tiles;
+      int fresh = 0;
       for (int s = 0; s < 27; ++s) {
         if (!((m >> s) & 1)) continue;
         const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
@@ -331,7 +334,16 @@ __device__ void visit3(const T3Args& a, int round, int T) {
         // the neighbour's halo part facing us (its side -d) changed
         const int32_t bits = (s == kT3Self) ? (kT3Active | kT3Full)
                                             : (kT3Active | (1 << (kT3SideShift + 26 - s)));
-        if (atomicOr(&fout[TN], bits) == 0) lout[atomicAdd(&a.counter[round + 1], 1)] = TN;
+        if (atomicOr(&fout[TN], bits) == 0) fresh |= 1 << s;
+      }
+      // one reservation for the newly activated tiles (the counter is one
+      // address for the whole chip)
+      if (fresh) {
+        int slot = atomicAdd(&a.counter[round + 1], __popc(fresh));
+        for (int s = 0; s < 27; ++s)
+          if ((fresh >> s) & 1)
+            lout[slot++] = P.tile_base + ((ttz + s / 9 - 1) * J.nty + (tty + (s / 3) % 3 - 1)) * J.ntx +
+                           (ttx + s % 3 - 1);
       }
     }
   }
@@ -358,7 +370,7 @@ size_t align256_t3(size_t x) { return (x + 255) & ~(size_t)255; }
 struct T3Plan {
   int tx = 0, tz = 0, lx = 0, lz = 0, n_tiles = 0, w_lds = 0;
   size_t off_jobs = 0, off_probs = 0, off_flags = 0, off_list = 0, off_counter = 0, off_err = 0,
-         total = 0;
+         off_stats = 0, total = 0;
   size_t lds = 0;
 };
 
@@ -399,6 +411,8 @@ int plan_t3(const Tile3Job* jobs, int n_jobs, const Tile3Prob* probs, int n_prob
   off += align256_t3((size_t)(max_rounds + 2) * sizeof(int32_t));
   P->off_err = off;
   off += 256;
+  P->off_stats = off;
+  off += align256_t3(kStatBytes);
   P->total = off;
   return CHERT_OK;
 }
@@ -472,7 +486,7 @@ int relax_tiles_3d(const Tile3Job* jobs, int n_jobs, const Tile3Prob* probs, int
   a.list = (int32_t*)(w + P.off_list);
   a.counter = (int32_t*)(w + P.off_counter);
   a.err = (int32_t*)(w + P.off_err);
-  a.stats = (unsigned long long*)(w + P.off_err + 64);
+  a.stats = (unsigned long long*)(w + P.off_stats);
   void (*kern)(T3Args, int) = push_group == 1 ? k_tile3_tau<1> : (push_group == 4 ? k_tile3_tau<4>
                                                                                    : k_tile3_tau<2>);
   const int threads = (P.tx * P.tx * P.tz + 63) / 64 * 64;
@@ -508,10 +522,12 @@ int relax_tiles_3d(const Tile3Job* jobs, int n_jobs, const Tile3Prob* probs, int
   }
   int32_t herr = 0;
   unsigned long long hs[2] = {0, 0};
+  std::vector<unsigned long long> slots((size_t)kStatSlots * kStatSlotU64);
   e = hipMemcpyAsync(&herr, a.err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(hs, a.stats, sizeof(hs), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(slots.data(), a.stats, kStatBytes, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+  stats_reduce(slots.data(), 2, 0u, hs);
   *rounds = done < 0 ? max_rounds : done;
   *visits = (int64_t)hs[0];
   *edges = (int64_t)hs[1];

@@ -150,7 +150,8 @@ struct RelaxArgs {
   int32_t* list;     // [2][n_tiles] tiles active in a round (by round parity)
   int32_t* counter;  // [max_rounds + 2] tiles active in each round
   int32_t* err;      // out-of-range class ids seen
-  unsigned long long* stats;  // [3 slots][2]: tile visits, raw edges (slot 2 unused)
+  unsigned long long* stats;  // [kStatSlots][16] shards of: [phase][visits, edges],
+                              // levels sum [6 + phase], levels max [9 + phase]
   int w_lds_doubles; // LDS room for W
   // Tile ordering (bucket > 0): a tile activated with key k (the smallest
   // value among the changed border nodes that woke it: tau, or the hop
@@ -179,10 +180,11 @@ __device__ __forceinline__ unsigned long long dbits(double x) {
 __device__ __forceinline__ void count_visit(const RelaxArgs& a, int phase, long long edges,
                                             int levels) {
   if (threadIdx.x == 0) {
-    atomicAdd(&a.stats[2 * phase], 1ull);
-    atomicAdd(&a.stats[2 * phase + 1], (unsigned long long)edges);
-    atomicAdd(&a.stats[6 + phase], (unsigned long long)levels);
-    atomicMax(&a.stats[9 + phase], (unsigned long long)levels);
+    unsigned long long* st = stat_slot(a.stats);
+    atomicAdd(&st[2 * phase], 1ull);
+    atomicAdd(&st[2 * phase + 1], (unsigned long long)edges);
+    atomicAdd(&st[6 + phase], (unsigned long long)levels);
+    atomicMax(&st[9 + phase], (unsigned long long)levels);
   }
 }
 
@@ -332,7 +334,7 @@ __global__ void k_trace_begin(int32_t* err, unsigned long long* stats, int32_t* 
     *abort_seen = 0;
   }
   if (threadIdx.x < 4) persist_result[threadIdx.x] = 0;
-  if (threadIdx.x < 12) stats[threadIdx.x] = 0ull;
+  for (int i = threadIdx.x; i < kStatSlots * kStatSlotU64; i += blockDim.x) stats[i] = 0ull;
 }
 
 // Class ids of a map outside [0, K): raise the error word, which every
@@ -484,6 +486,9 @@ __device__ __forceinline__ void activate(const RelaxArgs& a, int round, const Ti
     if (mask & (1 << 4)) key = 0ull;
     atomicMin(&a.pmin[((round + 1) % 3) * a.n_prob + c.p], key);
   }
+  // set the flags, then reserve list slots for the newly activated tiles
+  // with one atomic (the counter is one address for the whole chip)
+  int fresh = 0;
   for (int bit = 0; bit < 9; ++bit) {
     if (!(mask & (1 << bit))) continue;
     int dx = bit % 3 - 1, dz = bit / 3 - 1;
@@ -496,10 +501,14 @@ __device__ __forceinline__ void activate(const RelaxArgs& a, int round, const Ti
     if (a.bucket > 0.0)
       atomicMin(&a.key[(int64_t)((round + 1) & 1) * a.n_tiles + pr.tile_base + nz_ * jb.ntx + nx_],
                 key);
-    if (atomicOr(f, bits) == 0)
-      a.list[(int64_t)((round + 1) & 1) * a.n_tiles + atomicAdd(&a.counter[round + 1], 1)] =
-          pr.tile_base + nz_ * jb.ntx + nx_;
+    if (atomicOr(f, bits) == 0) fresh |= 1 << bit;
   }
+  if (!fresh) return;
+  int slot = atomicAdd(&a.counter[round + 1], __popc(fresh));
+  for (int bit = 0; bit < 9; ++bit)
+    if (fresh & (1 << bit))
+      a.list[(int64_t)((round + 1) & 1) * a.n_tiles + slot++] =
+          pr.tile_base + (c.tz + bit / 3 - 1) * jb.ntx + (c.tx + bit % 3 - 1);
 }
 
 // Smallest pending key of each problem for round + 2 starts over (round
@@ -1513,7 +1522,7 @@ struct Plan {
   std::vector<int> ntx, ntz, K;
   size_t off_star = 0, off_lbin = 0, off_jobs = 0, off_probs = 0, off_flags = 0, off_list = 0,
          off_counter = 0, off_key = 0, off_pmin = 0, off_wmin = 0,
-         off_err = 0, off_nkey = 0, off_tight = 0, total = 0;
+         off_err = 0, off_stats = 0, off_nkey = 0, off_tight = 0, total = 0;
   std::vector<size_t> off_W;  // per job
   std::vector<size_t> off_best;  // per job: closest-direction table (slowness caches)
   int w_lds_doubles = 0;
@@ -1651,6 +1660,8 @@ static int make_plan(const chert_trace_job* jobs, int n_jobs, const chert_trace_
   off += 256;
   P->off_err = off;
   off += 256;
+  P->off_stats = off;
+  off += align256(kStatBytes);
   for (int j = 0; j < n_jobs; ++j) {
     P->off_best.push_back(off);
     if (jobs[j].d->sampling == CHERT_SAMPLE_SLOWNESS)
@@ -1887,7 +1898,7 @@ static int prepare(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
   a.list = (int32_t*)(ws + P.off_list);
   a.counter = (int32_t*)(ws + P.off_counter);
   a.err = (int32_t*)(ws + P.off_err);
-  a.stats = (unsigned long long*)(ws + P.off_err + 64);
+  a.stats = (unsigned long long*)(ws + P.off_stats);
   a.w_lds_doubles = P.w_lds_doubles;
   a.key = (unsigned long long*)(ws + P.off_key);
   a.pmin = (unsigned long long*)(ws + P.off_pmin);
@@ -2066,13 +2077,15 @@ static int finish(const Prepared& Q, const chert_trace_opts* o, hipStream_t s, i
   int32_t herr = 0;
   int32_t hres[4] = {0, 0, 0, 0};
   unsigned long long hstats[12];
+  std::vector<unsigned long long> slots((size_t)kStatSlots * kStatSlotU64);
   hipError_t e = hipMemcpyAsync(&herr, a.err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(hstats, a.stats, sizeof(hstats), hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(slots.data(), a.stats, kStatBytes, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(hres, Q.pa.result, sizeof(hres), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+  stats_reduce(slots.data(), 12, 0xe00u, hstats);  // entries 9-11 are maxima
   const uint32_t outs = o->outputs;
   const bool ran[3] = {true, (outs & (CHERT_OUT_PRED_P | CHERT_OUT_PRED_A)) != 0, false};
   int status = CHERT_OK;
