@@ -473,7 +473,8 @@ struct WarmArgs {
   WinBracket* brs;              // their brackets, in scan order per direction
   int32_t* br_len;
   int64_t br_cap;
-  unsigned long long* stats;    // CHERT_WARM_NSTATS counters
+  unsigned long long* stats;    // CHERT_WARM_NSTATS counters (folded from shard)
+  unsigned long long* shard;    // [kStatSlots][16] per-slot partial counters
   double resid_tol;
 };
 
@@ -613,7 +614,7 @@ __global__ void __launch_bounds__(64) k_warm_solve(WarmArgs w) {
       dir_cols(a, sidx, &d, &col, &pcol);
       store_pair(a, row, col, pcol, none, 0.0, blocked);
     }
-    if (lane == 0) atomicAdd(&w.stats[0], 1ull);
+    if (lane == 0) atomicAdd(&stat_slot(w.shard)[0], 1ull);
     return;  // block-uniform
   }
   const Medium m = load_medium(c);
@@ -683,7 +684,7 @@ __global__ void __launch_bounds__(64) k_warm_solve(WarmArgs w) {
     }
   }
   __syncthreads();
-  if (lane < CHERT_WARM_NSTATS && s_cnt[lane]) atomicAdd(&w.stats[lane], (unsigned long long)s_cnt[lane]);
+  if (lane < CHERT_WARM_NSTATS && s_cnt[lane]) atomicAdd(&stat_slot(w.shard)[lane], (unsigned long long)s_cnt[lane]);
 }
 
 // Directions near a fold, for the jobs k_warm_solve listed: the plain
@@ -843,10 +844,10 @@ __global__ void __launch_bounds__(64) k_warm_window(WarmArgs w) {
       w.fb_list[atomicAdd(w.fb_len, 1)] = (int32_t)job;
     }
   }
-  if (lane == 0 && samples) atomicAdd(&w.stats[8], samples);
+  if (lane == 0 && samples) atomicAdd(&stat_slot(w.shard)[8], samples);
   if (lane == 0 && guard) {
-    atomicAdd(&w.stats[9], guard);
-    atomicAdd(&w.stats[1], guard);
+    atomicAdd(&stat_slot(w.shard)[9], guard);
+    atomicAdd(&stat_slot(w.shard)[1], guard);
   }
 }
 
@@ -937,7 +938,8 @@ struct Warm3Args {
   uint32_t* fold;               // [jobs][kFoldWords] fold bins of the elastic map
   int32_t* fb_list;             // job * n_dirs + direction, for the plain search
   int32_t* fb_len;
-  unsigned long long* stats;    // CHERT_WARM_NSTATS counters
+  unsigned long long* stats;    // CHERT_WARM_NSTATS counters (folded from shard)
+  unsigned long long* shard;    // [kStatSlots][16] per-slot partial counters
   double resid_tol;
 };
 
@@ -986,7 +988,7 @@ __global__ void __launch_bounds__(64) k_warm3_folds(Warm3Args w) {
   __syncthreads();
   if (threadIdx.x < kFoldWords)
     w.fold[job * kFoldWords + threadIdx.x] = s_all ? ~0u : s_fold[threadIdx.x];
-  if (threadIdx.x == 0) atomicAdd(&w.stats[0], 1ull);
+  if (threadIdx.x == 0) atomicAdd(&stat_slot(w.shard)[0], 1ull);
 }
 
 // one lane per (job, direction): Newton polish from the prediction and the
@@ -1057,7 +1059,7 @@ __global__ void __launch_bounds__(64) k_warm3_solve(Warm3Args w, int64_t n_rows)
   for (int q = 1; q < 8; ++q) {
     unsigned long long v = cnt[q];
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-    if (__lane_id() == 0 && v) atomicAdd(&w.stats[q], v);
+    if (__lane_id() == 0 && v) atomicAdd(&stat_slot(w.shard)[q], v);
   }
 }
 
@@ -1086,12 +1088,22 @@ __global__ void __launch_bounds__(64) k_warm3_plain(Warm3Args w) {
   }
 }
 
-__global__ void k_warm_zero(int32_t* fb_len, int32_t* win_len, unsigned long long* stats) {
+__global__ void k_warm_zero(int32_t* fb_len, int32_t* win_len, unsigned long long* shard) {
   if (threadIdx.x == 0) *fb_len = 0;
   if (threadIdx.x == 1) *win_len = 0;
   if (threadIdx.x == 2) win_len[1] = 0;  // fold directions
   if (threadIdx.x == 3) win_len[2] = 0;  // their brackets
-  if (threadIdx.x < CHERT_WARM_NSTATS) stats[threadIdx.x] = 0ull;
+  for (int i = threadIdx.x; i < kStatSlots * kStatSlotU64; i += blockDim.x) shard[i] = 0ull;
+}
+
+// the build's counters: the sums of their per-slot partials (the kernels
+// add into the slot of their workgroup, not into one address)
+__global__ void k_warm_stats_fold(const unsigned long long* shard, unsigned long long* stats) {
+  const int i = threadIdx.x;
+  if (i >= CHERT_WARM_NSTATS) return;
+  unsigned long long v = 0;
+  for (int q = 0; q < kStatSlots; ++q) v += shard[(size_t)q * kStatSlotU64 + i];
+  stats[i] = v;
 }
 
 __global__ void k_write_header(uint8_t* cache, int32_t dim, int32_t n_dirs, uint32_t mask,
@@ -1169,14 +1181,31 @@ __global__ void __launch_bounds__(256) k_cache_stats(const int32_t* status, cons
   nob = wave_sum(nob);
   unus = wave_sum(unus);
   mr = wave_max(mr);
+  // one set of atomics per workgroup (each counter is one address)
+  __shared__ unsigned long long s_v[4][7];
+  const int wv = threadIdx.x >> 6;
   if (__lane_id() == 0) {
-    atomicAdd((unsigned long long*)&st->n_entries, (unsigned long long)n);
-    atomicAdd((unsigned long long*)&st->n_converged, (unsigned long long)conv);
-    atomicAdd((unsigned long long*)&st->n_noconv, (unsigned long long)noconv);
-    atomicAdd((unsigned long long*)&st->n_illcond, (unsigned long long)ill);
-    atomicAdd((unsigned long long*)&st->n_nobracket, (unsigned long long)nob);
-    atomicAdd((unsigned long long*)&st->n_unusable, (unsigned long long)unus);
-    atomicMax((unsigned long long*)&st->max_resid, mr);
+    s_v[wv][0] = n;
+    s_v[wv][1] = conv;
+    s_v[wv][2] = noconv;
+    s_v[wv][3] = ill;
+    s_v[wv][4] = nob;
+    s_v[wv][5] = unus;
+    s_v[wv][6] = mr;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w2 = 1; w2 < (int)(blockDim.x >> 6); ++w2) {
+      for (int i = 0; i < 6; ++i) s_v[0][i] += s_v[w2][i];
+      s_v[0][6] = s_v[w2][6] > s_v[0][6] ? s_v[w2][6] : s_v[0][6];
+    }
+    atomicAdd((unsigned long long*)&st->n_entries, s_v[0][0]);
+    atomicAdd((unsigned long long*)&st->n_converged, s_v[0][1]);
+    atomicAdd((unsigned long long*)&st->n_noconv, s_v[0][2]);
+    atomicAdd((unsigned long long*)&st->n_illcond, s_v[0][3]);
+    atomicAdd((unsigned long long*)&st->n_nobracket, s_v[0][4]);
+    atomicAdd((unsigned long long*)&st->n_unusable, s_v[0][5]);
+    atomicMax((unsigned long long*)&st->max_resid, s_v[0][6]);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0)
     st->n_fallback = fb_len ? (int64_t)*fb_len * fb_entries : 0;
@@ -1192,7 +1221,7 @@ static void enqueue_cache_stats(const chert_cache_desc* d, int64_t n_classes, ui
   const int32_t* status = (const int32_t*)(cache + lay.status_offset);
   const double* res = (const double*)(cache + lay.fields_offset) + CHERT_F_RES * 3 * per_mode;
   int64_t blocks = (per_mode + 255) / 256;
-  if (blocks > 2048) blocks = 2048;
+  if (blocks > 512) blocks = 512;
   CHERT_LAUNCH("k_cache_stats_zero", k_cache_stats_zero, dim3(1), dim3(64), 0, s, d->stats_dev);
   CHERT_LAUNCH("k_cache_stats", k_cache_stats, dim3((unsigned)blocks), dim3(256), 0, s, status,
                res, per_mode, d->mode_mask, fb_len, fb_entries, d->stats_dev);
@@ -1413,7 +1442,8 @@ static size_t warm3_bytes(const chert_cache_desc* d, int64_t n_classes) {
   const size_t jobs = (size_t)n_jobs_of(d, n_classes);
   const size_t rows = jobs * (size_t)d->n_dirs;
   return al256(jobs * d->n_sweep * sizeof(double2)) + al256(rows * sizeof(float2)) +
-         al256(jobs * kFoldWords * sizeof(uint32_t)) + al256(rows * sizeof(int32_t)) + 256;
+         al256(jobs * kFoldWords * sizeof(uint32_t)) + al256(rows * sizeof(int32_t)) + 256 +
+         al256(kStatBytes);
 }
 
 extern "C" size_t chert_build_cache_surrogate_workspace_bytes(const chert_cache_desc* d,
@@ -1424,7 +1454,8 @@ extern "C" size_t chert_build_cache_surrogate_workspace_bytes(const chert_cache_
   const SolveArgs so = solve_args(d, nullptr, n_classes, nullptr, lay, nullptr);
   const size_t jobs = (size_t)n_jobs_of(d, n_classes);
   return al256(jobs * so.n_solve * sizeof(float2)) + 2 * al256(jobs * sizeof(int32_t)) + 256 +
-         al256(jobs * kDirsPerJob * sizeof(int4)) + al256(jobs * kBracketsPerJob * sizeof(WinBracket));
+         al256(jobs * kDirsPerJob * sizeof(int4)) + al256(jobs * kBracketsPerJob * sizeof(WinBracket)) +
+         al256(kStatBytes);
 }
 
 extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
@@ -1464,12 +1495,13 @@ extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
     ws += al256((size_t)rows * sizeof(int32_t));
     w.fb_len = (int32_t*)ws;
     w.stats = stats_dev ? (unsigned long long*)stats_dev : (unsigned long long*)(ws + 64);
+    w.shard = (unsigned long long*)(ws + 256);
     w.resid_tol = resid_tol > 0.0 ? resid_tol : 1e-11;
     CHERT_LAUNCH("k_write_header", k_write_header, dim3(1), dim3(64), 0, s, cache, d->dim,
                  d->n_dirs, d->mode_mask, d->kernel, d->n_sweep, d->n_subset, n_classes,
                  d->sampling);
-    CHERT_LAUNCH("k_warm_zero", k_warm_zero, dim3(1), dim3(64), 0, s, w.fb_len, w.fb_len + 1,
-                 w.stats);
+    CHERT_LAUNCH("k_warm_zero", k_warm_zero, dim3(1), dim3(256), 0, s, w.fb_len, w.fb_len + 1,
+                 w.shard);
     if (rows > 0) {
       SweepArgs sa{};
       sa.classes = classes_dev;
@@ -1491,6 +1523,8 @@ extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
       const int64_t pg = (rows + 63) / 64 < 8192 ? (rows + 63) / 64 : 8192;
       CHERT_LAUNCH("k_warm3_plain", k_warm3_plain, dim3((unsigned)pg), dim3(64), 0, s, w);
     }
+    CHERT_LAUNCH("k_warm_stats_fold", k_warm_stats_fold, dim3(1), dim3(64), 0, s,
+                 (const unsigned long long*)w.shard, w.stats);
     enqueue_cache_stats(d, n_classes, cache, lay, w.fb_len, 1, s);  // listed: directions
     return launch_status();
   }
@@ -1517,13 +1551,15 @@ extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
     w.brs = (WinBracket*)(tail + al256(jobs * kDirsPerJob * sizeof(int4)));
   }
   w.stats = stats_dev ? (unsigned long long*)stats_dev : (unsigned long long*)(w.fb_len + 16);
+  w.shard = (unsigned long long*)(ws + chert_build_cache_surrogate_workspace_bytes(d, n_classes) -
+                                  al256(kStatBytes));
   w.resid_tol = resid_tol > 0.0 ? resid_tol : 1e-11;
 
   CHERT_LAUNCH("k_write_header", k_write_header, dim3(1), dim3(64), 0, s, cache, d->dim,
                d->n_dirs, d->mode_mask, d->kernel, d->n_sweep, d->n_subset, n_classes,
                  d->sampling);
-  CHERT_LAUNCH("k_warm_zero", k_warm_zero, dim3(1), dim3(64), 0, s, w.fb_len, w.win_len,
-               w.stats);
+  CHERT_LAUNCH("k_warm_zero", k_warm_zero, dim3(1), dim3(256), 0, s, w.fb_len, w.win_len,
+               w.shard);
   if (jobs > 0 && rows > 0) {
     const int64_t blocks = (rows + mlp::kInferRows - 1) / mlp::kInferRows;
     if (blocks > 0x7fffffffLL) return fail(CHERT_ERR_INVALID_ARG, "too many entries");
@@ -1540,6 +1576,8 @@ extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
                  (size_t)d->n_sweep * sizeof(double2), s, w.so, (const int32_t*)w.fb_list,
                  (const int32_t*)w.fb_len, jobs);
   }
+  CHERT_LAUNCH("k_warm_stats_fold", k_warm_stats_fold, dim3(1), dim3(64), 0, s,
+               (const unsigned long long*)w.shard, w.stats);
   enqueue_cache_stats(d, n_classes, cache, lay, w.fb_len, w.so.n_cols, s);  // listed: jobs
   return launch_status();
 }
