@@ -454,6 +454,20 @@ def _elapsed(torch, ev, stream):
     return ev[0].elapsed_time(ev[1]) * 1e-3
 
 
+def _batch_relax_profile(C, torch, call, kernel):
+    """One more call of a batched trace with the library's per-kernel timers
+    on for `kernel` and statistics: (kernel seconds, pair relaxations,
+    launches)."""
+    st = C.TraceStats()
+    C.chert_prof_enable(True, only=kernel)
+    call(st)
+    torch.cuda.synchronize()
+    prof = C.chert_prof_read()
+    C.chert_prof_enable(False)
+    n, ms = prof.get(kernel, (0, 0.0))
+    return ms * 1e-3, st.edge_relaxations[0], n
+
+
 def _converged(status):
     ok = (status & (1 | 4 | 8)) == 0  # not NO_BRACKET / FLUID / NONPHYS
     return int(ok.sum())
@@ -1453,7 +1467,8 @@ def run_cells(args):
     bsrc = [int(x) for x in np.linspace(0, ncx, n_batch).astype(int) * cn]
     bres = {}
     for bw in (0.0, 16.0):
-        tot = 0.0
+        tot = rk_s = 0.0
+        rk_p = rk_n = 0
         for mode in m.modes:
             o = C.trace_opts(outs, bucket_width=bw)
             t = {k: torch.empty((n_batch, n), dtype=dt, device=dev) for k, dt in
@@ -1467,20 +1482,32 @@ def run_cells(args):
             C.chert_trace_cells(desc, cache, K, cg, mode, bsrc, o, t["tr"], t["ti"], t["ts"],
                                 t["pp"], t["pa"], tws, stream=stream)
             tot += _elapsed(torch, ev, stream)
+
+            def call(st, o_bw=bw, t=t, tws=tws, mode=mode):
+                C.chert_trace_cells(desc, cache, K, cg, mode, bsrc,
+                                    C.trace_opts(outs, bucket_width=o_bw, stats=st), t["tr"],
+                                    t["ti"], t["ts"], t["pp"], t["pa"], tws, stream=stream)
+            ks, kp, kn = _batch_relax_profile(C, torch, call, "k_cell_relax")
+            rk_s += ks
+            rk_p += kp
+            rk_n += kn
         bres[f"bucket_{bw:g}"] = {"s_all_modes": tot,
-                                  "fields_per_s": len(m.modes) * n_batch / tot}
+                                  "fields_per_s": len(m.modes) * n_batch / tot,
+                                  "relax_kernel_s": rk_s, "relax_kernel_pairs": rk_p,
+                                  "relax_kernel_launches": rk_n}
     res["batch_16_sources"] = bres
-    best = min(per.values(), key=lambda r: sum(v["s"] for v in r.values()))
     res["value"] = max(v["fields_per_s"] for v in bres.values())
     res["unit"] = ("fields/s (tau_R, tau_I, predecessors and t* per source and mode, "
                    "16 sources per call, cell network)")
     res["higher_is_better"] = True
-    # ALU roofline of the pair relaxation: one add and one compare per pair
-    dom = max(best.values(), key=lambda v: v["relax_kernel_s"])
+    # ALU roofline of the pair relaxation in the batch the value is quoted
+    # on: one add and one compare per pair
+    dom = max(bres.values(), key=lambda v: v["fields_per_s"])
     ach = 2.0 * dom["relax_kernel_pairs"] / max(dom["relax_kernel_s"], 1e-12) / 1e12
     res["roofline"] = {"bound": "alu", "achieved": ach, "peak": FP64_VALU_PEAK_TOPS,
                        "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK_TOPS, "traffic": None,
-                       "kernel": "k_cell_relax"}
+                       "kernel": "k_cell_relax",
+                       "avg_launch_us": 1e6 * dom["relax_kernel_s"] / max(dom["relax_kernel_launches"], 1)}
     if not args.no_cpu:
         import oracle as O
         cls_np = np.stack([O.class_from_thomsen(*L.thomsen_args()) for L in m.layers])
@@ -1590,7 +1617,8 @@ def run_blocks(args):
     bsrc = [int(x) for x in rng.choice(surf, n_batch, replace=False)]
     bres = {}
     for bw in (0.0, 4.0):
-        tot = 0.0
+        tot = rk_s = 0.0
+        rk_p = rk_n = 0
         for mode in m.modes:
             o = C.trace_opts(outs, bucket_width=bw)
             t = bufs(n_batch)
@@ -1602,19 +1630,31 @@ def run_blocks(args):
             C.chert_trace_blocks(desc, cache, K, bg, mode, bsrc, o, t["tr"], t["ti"], t["ts"],
                                  t["pp"], t["pa"], tws, stream=stream)
             tot += _elapsed(torch, ev, stream)
+
+            def call(st, o_bw=bw, t=t, tws=tws, mode=mode):
+                C.chert_trace_blocks(desc, cache, K, bg, mode, bsrc,
+                                     C.trace_opts(outs, bucket_width=o_bw, stats=st), t["tr"],
+                                     t["ti"], t["ts"], t["pp"], t["pa"], tws, stream=stream)
+            ks, kp, kn = _batch_relax_profile(C, torch, call, "k_block_relax")
+            rk_s += ks
+            rk_p += kp
+            rk_n += kn
         bres[f"bucket_{bw:g}"] = {"s_all_modes": tot,
-                                  "fields_per_s": len(m.modes) * n_batch / tot}
+                                  "fields_per_s": len(m.modes) * n_batch / tot,
+                                  "relax_kernel_s": rk_s, "relax_kernel_pairs": rk_p,
+                                  "relax_kernel_launches": rk_n}
     res["batch_16_sources"] = bres
     res["value"] = max(v["fields_per_s"] for v in bres.values())
     res["unit"] = ("fields/s (tau_R, tau_I, predecessors and t* per source and mode, "
                    "16 sources per call, block network)")
     res["higher_is_better"] = True
-    best = min(per.values(), key=lambda r: sum(v["s"] for v in r.values()))
-    dom = max(best.values(), key=lambda v: v["relax_kernel_s"])
+    # ALU roofline of the pair relaxation in the batch the value is quoted on
+    dom = max(bres.values(), key=lambda v: v["fields_per_s"])
     ach = 2.0 * dom["relax_kernel_pairs"] / max(dom["relax_kernel_s"], 1e-12) / 1e12
     res["roofline"] = {"bound": "alu", "achieved": ach, "peak": FP64_VALU_PEAK_TOPS,
                        "unit": "TFLOP/s", "frac": ach / FP64_VALU_PEAK_TOPS, "traffic": None,
-                       "kernel": "k_block_relax"}
+                       "kernel": "k_block_relax",
+                       "avg_launch_us": 1e6 * dom["relax_kernel_s"] / max(dom["relax_kernel_launches"], 1)}
     if not args.no_cpu:
         import oracle as O
         cls_np = np.stack([O.class_from_thomsen(*L.thomsen_args()) for L in m.layers])
