@@ -52,13 +52,13 @@ FP64_VALU_PEAK_TOPS = 39.3  # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz, one o
 # Valid only for the kernel source it was measured on.
 MEASURED_TRAFFIC = {
     "source": "paper_2609_26108_amd/csrc/trace.hip",
-    "source_sha256_16": "d6118042267799b1",
+    "source_sha256_16": "953ac49953088a6b",
     "fetch_scale": 2.0, "write_scale": 1.0,
     # workload -> kernel -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
     # (profiles/k_relax_tau__shots_4_grids_per_node.md: one step, 16 x 64
     # tiles, push group 4, 112 dispatches of each relaxation kernel)
-    "kib_per_dispatch": {"shots": {"k_relax_tau": (787997.56, 10540.48),
-                                   "k_relax_tree": (247162.04, 34302.97)}},
+    "kib_per_dispatch": {"shots": {"k_relax_tau": (789838.42, 10509.06),
+                                   "k_relax_tree": (256364.75, 40187.29)}},
 }
 
 
