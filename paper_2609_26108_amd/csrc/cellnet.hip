@@ -830,9 +830,9 @@ __global__ void __launch_bounds__(kLvlThreads) k_cell_level(CellArgs a, int L) {
       if (ts) ts[j] = ts[b] + seg_weight<MSPM, D3>(a, 1, MSPM ? common_cell(a, b, j) : 0, b, j);
     }
   }
-  // any append keeps the BFS going; a plain store of 1 by the workgroups
-  // that appended (the host only tests for zero)
-  if (threadIdx.x == 0 && s_any) *a.alive = 1;
+  // any append keeps the BFS going: the workgroups that appended raise the
+  // level count to L + 2 (levels 0 .. L + 1 hold nodes)
+  if (threadIdx.x == 0 && s_any) atomicMax(a.alive, L + 2);
 }
 
 __global__ void k_cell_zero(int32_t* x) { *x = 0; }
@@ -1403,7 +1403,8 @@ int trace_cells_impl(const CellSrc& w, int64_t n_classes, const CellGeo& G, int3
   }
   if (rounds < 0) return fail(CHERT_ERR_NO_CONVERGENCE, "round cap reached");
 
-  // predecessors and t*: one launch per level, the host checking every 8
+  // predecessors and t*: one launch per level, the host checking between
+  // groups of levels
   int levels = 0;
   if (a.tree_mask) {
     // few workgroups per problem: each reserves its staged appends with one
@@ -1411,9 +1412,14 @@ int trace_cells_impl(const CellSrc& w, int64_t n_classes, const CellGeo& G, int3
     unsigned gx = (unsigned)(1024 / P.n_prob);
     if (gx < 1) gx = 1;
     if (gx > 128) gx = 128;
+    int deepest = 1;  // levels holding nodes (the source's level 0 at least)
     for (int Lv = 0;;) {
+      // groups of 8, then 16, then 32 levels between host checks (a group
+      // with no append ends the BFS; predecessors trail by one level, so
+      // any group of at least two levels finalises the last one)
+      const int group = Lv < 16 ? 8 : (Lv < 48 ? 16 : 32);
       CHERT_LAUNCH("k_cell_zero", k_cell_zero, dim3(1), dim3(1), 0, s, a.alive);
-      for (int q = 0; q < 8; ++q, ++Lv)
+      for (int q = 0; q < group; ++q, ++Lv)
         if (w.mspm)
           CHERT_LAUNCH("k_cell_level", (k_cell_level<true, false>), dim3(gx, (unsigned)P.n_prob),
                        dim3(kLvlThreads), 0, s, a, Lv);
@@ -1430,9 +1436,10 @@ int trace_cells_impl(const CellSrc& w, int64_t n_classes, const CellGeo& G, int3
       if (o->abort_flag_host && *o->abort_flag_host)
         return fail(CHERT_ERR_ABORTED, "aborted by the caller");
       if (alive == 0) {
-        levels = Lv;
+        levels = deepest;
         break;
       }
+      deepest = alive > deepest ? alive : deepest;
       if (Lv > P.n + 16) return fail(CHERT_ERR_HIP, "BFS did not end");
     }
   }

@@ -18,6 +18,18 @@ from test_oracle_slow import random_slow_cache  # noqa: E402
 KEYS = ("tauR", "tauI", "tstar", "predP", "predA")
 
 
+def tree_levels(pred, src):
+    """Levels of a predecessor tree (hop of its deepest node + 1)."""
+    h = np.full(pred.size, -1, np.int64)
+    h[src] = 0
+    while True:
+        m = (h < 0) & (pred >= 0)
+        m[m] = h[pred[m]] >= 0
+        if not m.any():
+            return int(h.max()) + 1
+        h[m] = h[pred[m]] + 1
+
+
 @pytest.fixture(scope="module")
 def G():
     if not torch.cuda.is_available():
@@ -66,6 +78,10 @@ def test_ray_cache_bitwise(G, cn, ncx, ncz, bucket):
             o = O.trace_cells_2d(ncx, ncz, cn, h, 0.8 * h, cid, f[:, mode], s[mode], src)
             for key in KEYS:
                 assert np.array_equal(g[key][si], o[key]), (mode, si, key)
+        # the reported BFS depth is the deepest predecessor tree of the call
+        deepest = max(tree_levels(g[k][si], src) for si, src in enumerate(srcs)
+                      for k in ("predP", "predA"))
+        assert st.rounds[1] == deepest, (st.rounds[1], deepest)
 
 
 @pytest.mark.parametrize("cn,bucket", [(4, 0.0), (6, 16.0)])
