@@ -1052,7 +1052,28 @@ def cpu_baseline_shots(grids, solves_total, node_fields_total, shots, opts):
     cache_rate = n_solves / t_cache                 # unique solves per second
     trace_rate = 2 * n / t_trace                    # problem nodes per second
     t_step = solves_total / cache_rate + node_fields_total / trace_rate
+    # the same oracle on every host core over independent tasks (node chunks
+    # of the cache sample; one shot and mode per Dijkstra); the oracle's C
+    # calls release the interpreter lock, so threads run them in parallel
+    from concurrent.futures import ThreadPoolExecutor
+    T = max(1, min(16, os.cpu_count() or 1))
+    chunks = [c for c in np.array_split(np.arange(len(pick)), T) if c.size]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(T) as ex:
+        list(ex.map(lambda c: O.build_cache_2d(cls[c], mode_mask=0b011, subset=sub), chunks))
+    t_cache_T = time.perf_counter() - t0
+    tasks = [(m.sources[k % len(m.sources)], k % 2) for k in range(T)]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(T) as ex:
+        list(ex.map(lambda t: O.trace_2d(m.nx, m.nz, m.hx, m.hz, None, m.radius, fp[0][t[1]],
+                                         fp[1][t[1]], sp[t[1]], t[0], 360, sub, False), tasks))
+    t_trace_T = time.perf_counter() - t0
+    t_step_T = (solves_total / (n_solves / t_cache_T) +
+                node_fields_total / (len(tasks) * n / t_trace_T))
     return {"value": shots / t_step, "unit": "shots/s (extrapolated whole step)", "cores": 1,
+            "all_cores": {"value": shots / t_step_T, "cores": T,
+                          "sample": f"the cache sample split over {len(chunks)} threads; "
+                                    f"{len(tasks)} single-shot Dijkstras (tau_R, pred, t*) at once"},
             "kind": "oracle",
             "sample": f"plain cache build of {len(pick)} solid nodes of the 401x201 grid (qP+qSV, "
                       "80 star bins) and Dijkstra (tau_R, pred, t*) of its first shot in both "
@@ -1611,6 +1632,15 @@ def run_blocks(args):
                               "max_tau_R_s": far}
         per[f"bucket_{bw:g}"] = row
     res["modes"] = per
+    # raypaths (eqs 25, 33-34) of the centre shot to the 361 surface
+    # receivers, both fields, from the last traced mode's predecessors
+    pp, pa = t["pp"][0].cpu().numpy(), t["pa"][0].cpu().numpy()
+    t0 = time.perf_counter()
+    lens = [len(C.chert_extract_raypath(pr, m.sources[0], r)) for pr in (pp, pa)
+            for r in m.receivers]
+    res["raypaths"] = {"receivers": len(m.receivers), "paths": len(lens),
+                       "mean_nodes": float(np.mean(lens)), "max_nodes": int(np.max(lens)),
+                       "host_s": time.perf_counter() - t0}
     n_batch = 16
     rng = np.random.default_rng(16)
     surf = [ix_ + NX * iy_ for iy_ in range(0, NY, cn) for ix_ in range(0, NX, cn)]

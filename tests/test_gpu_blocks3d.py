@@ -123,7 +123,7 @@ def test_compact_3d_tti_full_size(G):
     random cache of the full 41253 Fibonacci directions (every column a
     different value, so the closest-direction pick over all of them is
     checked): the centre source, both fields, every output bitwise against
-    the oracle's Dijkstra."""
+    the oracle's Dijkstra, and the raypaths to the 361 surface receivers."""
     C = _C()
     m = W.blocks_3d()
     K = len(m.layers)
@@ -142,6 +142,16 @@ def test_compact_3d_tti_full_size(G):
             assert np.array_equal(g[key][0], o[key]), (mode, key)
         _, _, _, mask = O.block_lattice(m.ncx, m.ncy, m.ncz, m.block_n)
         assert np.isfinite(g["tauR"][0][mask.reshape(-1)]).all()
+        # raypaths (eqs 25, 33-34) to the 361 surface receivers from the
+        # GPU's predecessors equal the oracle's from its own, segment by
+        # segment, for both fields
+        src = m.sources[0]
+        for key in ("predP", "predA"):
+            for rcv in m.receivers:
+                path = C.chert_extract_raypath(g[key][0], src, rcv)
+                rc, ref = O.raypath(o[key], src, rcv)
+                assert rc == 0 and np.array_equal(path, ref), (mode, key, rcv)
+                assert path[0] == src and path[-1] == rcv
 
 
 def test_gpu_cache_end_to_end(G):
