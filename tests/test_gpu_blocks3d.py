@@ -230,3 +230,56 @@ def test_errors(G, small_cache):
     assert e.value.code == C.ERR_INVALID_ARG
     torch.cuda.synchronize()
     assert (out == -7.0).all()
+
+
+@pytest.mark.parametrize("cn,nc", [(1, (1, 1, 1)), (3, (1, 1, 1)), (2, (1, 5, 1)), (3, (4, 1, 2))])
+def test_degenerate_networks_bitwise(G, small_cache, cn, nc):
+    """One block, one row of blocks along y, one layer of blocks; sources on
+    the two far lattice corners and the same source twice in one call: every
+    output bitwise against the oracle, duplicate rows identical."""
+    C = _C()
+    f, s = small_cache
+    desc = C.cache_desc(n_dirs=400, modes=(0, 1), dim=3)
+    cache = G.import_cache(f, s, desc, 3)
+    ncx, ncy, ncz = nc
+    NX, NY, NZ, _ = O.block_lattice(ncx, ncy, ncz, cn)
+    cid = banded(NX, NY, NZ, 3, 2)
+    srcs = [0, NX * NY * NZ - 1, 0]
+    for mode in (0, 1):
+        g = G.trace_blocks(cache, desc, 3, ncx, ncy, ncz, cn, 9.0, 11.0, 10.0, cid, mode, srcs)
+        for si, src in enumerate(srcs):
+            o = O.trace_blocks_3d(ncx, ncy, ncz, cn, 9.0, 11.0, 10.0, cid, f[0, mode], f[1, mode],
+                                  s[mode], src, N=400)
+            for key in KEYS:
+                assert np.array_equal(g[key][si], o[key]), (mode, si, key)
+        for key in KEYS:
+            assert np.array_equal(g[key][0], g[key][2])
+
+
+def test_fluid_layer_blocks_shear_bitwise(G):
+    """A fluid layer between two tilted solids: qSV weights touching it are
+    +inf, so its nodes and the solid below stay unreached; qP passes.  Every
+    output bitwise against the oracle."""
+    C = _C()
+    solid = tti3_classes(2)
+    fluid = O.class_from_moduli(2.25e6, 2.25e6, 2.25e6, 0.0, 0.0, *[1000.0] * 5)
+    cls = np.stack([solid[0], fluid, solid[1]])
+    f, s = O.build_cache_3d(cls, N=400, mode_mask=0b011)
+    desc = C.cache_desc(n_dirs=400, modes=(0, 1), dim=3)
+    cache = G.import_cache(f, s, desc, 3)
+    ncx, ncy, ncz, cn = 4, 3, 6, 2
+    NX, NY, NZ, mask = O.block_lattice(ncx, ncy, ncz, cn)
+    z = np.arange(NZ)[:, None, None]
+    cid = np.broadcast_to(np.clip(z * 3 // NZ, 0, 2), (NZ, NY, NX)).astype(np.int32).copy()
+    srcs = [NX // 2 + NX * (NY // 2)]
+    for mode in (0, 1):
+        g = G.trace_blocks(cache, desc, 3, ncx, ncy, ncz, cn, 10.0, 10.0, 10.0, cid, mode, srcs)
+        o = O.trace_blocks_3d(ncx, ncy, ncz, cn, 10.0, 10.0, 10.0, cid, f[0, mode], f[1, mode],
+                              s[mode], srcs[0], N=400)
+        for key in KEYS:
+            assert np.array_equal(g[key][0], o[key]), (mode, key)
+        fl = (cid.reshape(-1) == 1) & mask.reshape(-1)
+        if mode == 1:
+            assert np.isinf(g["tauR"][0][fl]).all() and (g["predP"][0][fl] == -1).all()
+        else:
+            assert np.isfinite(g["tauR"][0][fl]).all()

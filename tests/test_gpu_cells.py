@@ -226,3 +226,54 @@ def test_full_size_layered_network_bitwise(G, bucket):
     o = O.trace_cells_2d(ncx, ncz, cn, m.hx, m.hz, m.class_id, f[:, 1], s[1], m.sources[0])
     for key in KEYS:
         assert np.array_equal(g[key][0], o[key]), key
+
+
+@pytest.mark.parametrize("cn,ncx,ncz", [(1, 1, 1), (16, 1, 1), (3, 1, 7), (4, 9, 1)])
+def test_degenerate_networks_bitwise(G, cn, ncx, ncz):
+    """One cell, one row or one column of cells; sources on the two far
+    lattice corners and the same source twice in one call: every output
+    bitwise against the oracle, duplicate rows identical."""
+    C = _C()
+    cls = tti_classes()
+    f, s = O.build_cache_2d(cls, n_dirs=360, mode_mask=0b011)
+    desc = C.cache_desc(n_dirs=360, modes=(0, 1))
+    cache = G.import_cache(f, s, desc, 3)
+    NX, NZ, _ = O.cell_lattice(ncx, ncz, cn)
+    cid = layered_cells(ncx, ncz, cn, 3, 0)
+    srcs = [0, NX * NZ - 1, 0]
+    for mode in (0, 1):
+        g = G.trace_cells(cache, desc, 3, ncx, ncz, cn, 10.0, 7.0, cid, mode, srcs)
+        for si, src in enumerate(srcs):
+            o = O.trace_cells_2d(ncx, ncz, cn, 10.0, 7.0, cid, f[:, mode], s[mode], src)
+            for key in KEYS:
+                assert np.array_equal(g[key][si], o[key]), (mode, si, key)
+        for key in KEYS:
+            assert np.array_equal(g[key][0], g[key][2])
+
+
+def test_fluid_layer_blocks_shear_bitwise(G):
+    """A fluid layer (no shear modulus) between two solids: qSV segments
+    touching it have no cached entry (+inf weight), so the fluid nodes and
+    the solid below them stay unreached while qP passes; every output
+    bitwise against the oracle."""
+    C = _C()
+    solid = tti_classes(2)
+    fluid = O.class_from_moduli(2.25e6, 2.25e6, 2.25e6, 0.0, 0.0, *[1000.0] * 5)
+    cls = np.stack([solid[0], fluid, solid[1]])
+    f, s = O.build_cache_2d(cls, n_dirs=360, mode_mask=0b011)
+    desc = C.cache_desc(n_dirs=360, modes=(0, 1))
+    cache = G.import_cache(f, s, desc, 3)
+    ncx, ncz, cn = 10, 9, 4
+    NX, NZ, mask = O.cell_lattice(ncx, ncz, cn)
+    cid = layered_cells(ncx, ncz, cn, 3, 0)
+    srcs = [NX // 2]
+    for mode in (0, 1):
+        g = G.trace_cells(cache, desc, 3, ncx, ncz, cn, 10.0, 10.0, cid, mode, srcs)
+        o = O.trace_cells_2d(ncx, ncz, cn, 10.0, 10.0, cid, f[:, mode], s[mode], srcs[0])
+        for key in KEYS:
+            assert np.array_equal(g[key][0], o[key]), (mode, key)
+        fl = (cid.reshape(-1) == 1) & mask.reshape(-1)
+        if mode == 1:
+            assert np.isinf(g["tauR"][0][fl]).all() and (g["predP"][0][fl] == -1).all()
+        else:
+            assert np.isfinite(g["tauR"][0][fl]).all()
