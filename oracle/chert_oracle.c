@@ -37,6 +37,15 @@
  *   - Edge weights: endpoint-averaged velocity and attenuation (eqs 28-30) at
  *     the bin of the edge direction; propagation and attenuation are two
  *     independent shortest-path problems (eqs 24, 31).
+ *   - Predecessors: the tight neighbour with the fewest BFS hops over tight
+ *     edges, then the lowest offset index (forward star) or node index (cell
+ *     network); t* folds the attenuation weights along that tree.
+ *   - Cell network (O-18): nodes on cell edges, every boundary pair of a cell
+ *     a segment; the block marching is re-entrant (a cell returns to the heap
+ *     whenever one of its nodes improves).  In 3D (O-20) the cells are blocks
+ *     and the nodes lie on their faces.
+ *   - MSPM (O-19): corner quantities solved at the segment's exact
+ *     direction; nodes between two corners interpolate them linearly.
  */
 #include <complex.h>
 #include <math.h>
