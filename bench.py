@@ -84,9 +84,9 @@ def measured_traffic_bytes(kernel, workload="layered"):
 MEASURED_FP64 = {
     "sources": ["paper_2609_26108_amd/csrc/cache_build.hip",
                 "paper_2609_26108_amd/csrc/physics.h", "paper_2609_26108_amd/csrc/mlp.h"],
-    "sources_sha256_16": "78bc2904204b923e",
-    "flops_per_dispatch": {"k_warm_solve": 4.9490e11, "k_warm_window": 2.8717e11,
-                           "k_warm_fold": 1.3793e10, "k_warm_predict": 5.3496e9},
+    "sources_sha256_16": "db564de836b3570d",
+    "flops_per_dispatch": {"k_warm_solve": 4.9490e11, "k_warm_window": 2.8714e11,
+                           "k_warm_fold": 2.1870e10, "k_warm_predict": 5.3496e9},
 }
 
 
