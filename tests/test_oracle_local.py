@@ -432,3 +432,43 @@ def test_jump_brackets_never_beat_roots(rock_table):
         for d in (26, 77, 206, 257, 130):
             tr, ti = f[5, O.QSV, k, d], f[6, O.QSV, k, d]
             assert abs(O.theta_imag(cls[k], O.QSV, tr, reading=O.OEV) - ti) < 1e-12
+
+
+@pytest.mark.parametrize("eps,delta,q", [(0.4, -0.2, np.inf), (0.3, -0.1, 30.0),
+                                         (0.5, 0.0, 20.0), (0.2, 0.1, 60.0)])
+def test_ill_flag_follows_the_chosen_bracket(eps, delta, q):
+    """The ILL status bit marks an entry whose chosen root sits in a sweep
+    bracket where the ray-angle map is nearly flat: |psi_b - psi_a| over
+    |theta_R,b - theta_R,a| below 1e-2.  Recomputed here from the sweep
+    table alone (the bracket holding the stored theta_R whose ends straddle
+    the target), for every qSV direction of strongly anisotropic classes."""
+    c = O.class_from_thomsen(3000.0, 1500.0, 2300, eps, delta, 0.1, 0.0, 0.0, q, q)
+    f, st = O.build_cache_2d(c, mode_mask=0b010)
+    thR, thI, psi, ok = O.sweep(c, O.QSV)
+    M = thR.size
+    tb_all = np.append(thR[1:], thR[0] + 2 * np.pi)
+    checked = 0
+    for d in range(360):
+        s = st[O.QSV, 0, d]
+        if s & O.ST_NO_BRACKET:
+            continue
+        target = wrap(np.radians(d))
+        tr = f[5, O.QSV, 0, d] % (2 * np.pi)
+        if tr < thR[0]:  # the bracket that wraps past 2 pi
+            tr += 2 * np.pi
+        slope = None
+        for j in range(M):
+            if not (ok[j] and ok[(j + 1) % M]):
+                continue
+            ta, tb = thR[j], tb_all[j]
+            if not (ta - 1e-12 <= tr <= tb + 1e-12):
+                continue
+            fa, fb = wrap(psi[j] - target), wrap(psi[(j + 1) % M] - target)
+            if abs(fb - fa) >= np.pi or (fa < 0) == (fb < 0):
+                continue
+            slope = (fb - fa) / (tb - ta)
+            break
+        assert slope is not None, d
+        assert bool(s & O.ST_ILL) == (abs(slope) < 1e-2), (d, slope, s)
+        checked += 1
+    assert checked > 300
