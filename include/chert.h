@@ -333,8 +333,10 @@ typedef struct chert_trace_stats {
  * CHERT_LAUNCH_PER_ROUND runs the traveltimes on 3D tiles of tile_x x
  * tile_x x tile_z nodes (default 8 x 8 x 8; at least radius per side, at
  * most 1024 nodes; the same per-round scheme, 26 neighbour tiles) and the
- * predecessors and t* with the frontier's BFS layers; _PERSISTENT is
- * UNSUPPORTED in 3D.
+ * predecessors and t* with the frontier's BFS layers; _PERSISTENT runs
+ * the same 3D tiles in one launch (an occupancy-sized grid, rounds
+ * separated by the bounded device-wide barrier, the abort word polled by
+ * the kernel) and the same BFS layers.
  * In per-node mode (no class map) the relaxation may read an edge's weight
  * from either endpoint's row; both hold the same value because a cache
  * stores direction d + n_dirs/2 as the exact copy of d. */
@@ -359,7 +361,8 @@ typedef struct chert_trace_opts {
                          the hop count with the width in hops) is visited
                          only once k <= its problem's smallest pending key
                          + width; otherwise it stays active for a later
-                         round.  The fields do not depend on it.          */
+                         round (2D tiles; the 3D tiles have no
+                         ordering).  The fields do not depend on it.      */
   chert_trace_stats *stats_host; /* nullable: filled when the call returns */
   const volatile int32_t *abort_flag_host; /* nullable caller-owned word in
                          pinned host memory (hipHostMalloc).  While it is
@@ -430,10 +433,11 @@ int chert_trace_batch(const chert_trace_job *jobs, int32_t n_jobs,
  * fields); only the time does.  Candidates: in 3D the frontier iteration
  * with bucket widths 0 (one bucket), 4, 16, 32, 64, 128, 256 (units of the
  * smallest edge weight) and the 3D tiles 8x8x8, 8x8x16, 16x16x4, 4x4x16
- * with push groups 1, 2, 4; in 2D the frontier with widths 16 and 64 and the
- * tiles 32x32, 64x16, 16x64, 32x16, 16x32, 128x8, 16x16 with push groups 1, 2, 4, 8,
- * per-round and persistent launch, then, if tiles win, their ordering width
- * 16, 64 or 256 on the fastest shape.  Each is timed (HIP events,
+ * with push groups 1, 2, 4, per-round and persistent launch; in 2D the
+ * frontier with widths 16 and 64 and the tiles 32x32, 64x16, 16x64, 32x16,
+ * 16x32, 128x8, 16x16 with push groups 1, 2, 4, 8, per-round and
+ * persistent launch, then, if tiles win, their ordering width 16, 64 or 256
+ * on the fastest shape.  Each is timed (HIP events,
  * second of two runs) on a probe batch made of the first source of every
  * job; the fastest is written into o->tile_x, tile_z, push_group, launch and
  * bucket_width (other fields are kept) and its probe time into *best_ms

@@ -91,8 +91,9 @@ int enqueue_wmin(const double* W, int64_t per_field, double* wmin, hipStream_t s
 // 3D tiles for the traveltime phase of a 3D batch (tile3d.hip): one job per
 // grid (class map, class-pair table [2][K][K][n_off] on the device), one
 // problem per (source, field).  The star offsets are device arrays.  Runs the
-// rounds to convergence on s (host checks every 8 rounds); tau must hold its
-// initial values (0 at the source, +inf elsewhere).
+// rounds to convergence on s (host checks every 8 rounds, or every round in
+// one persistent launch when `persistent`); tau must hold its initial values
+// (0 at the source, +inf elsewhere).
 struct Tile3Job {
   int nx, ny, nz, K;
   const int32_t* cls;
@@ -109,7 +110,7 @@ int relax_tiles_3d(const Tile3Job* jobs, int n_jobs, const Tile3Prob* probs, int
                    const int32_t* ox_dev, const int32_t* oy_dev, const int32_t* oz_dev, int n_off,
                    int R, int tile_x, int tile_z, int push_group, int max_rounds, void* ws,
                    size_t ws_bytes, hipStream_t s, const volatile int32_t* abort_flag,
-                   int* rounds, int64_t* visits, int64_t* edges);
+                   bool persistent, int* rounds, int64_t* visits, int64_t* edges);
 
 // Raise *err if any of the n class ids lies outside [0, K) (trace.hip).
 int enqueue_class_check(const int32_t* cls, int64_t n, int K, int32_t* err, hipStream_t s);

@@ -578,9 +578,8 @@ static int make_plan_f(const chert_trace_job* jobs, int n_jobs, const chert_trac
   off += (o->bucket_width > 0.0) ? align256((size_t)2 * P->cap * sizeof(int64_t)) : 0;
   P->off_thr = off;
   off += align256((size_t)2 * P->n_prob * sizeof(double) + 4 * sizeof(double));
-  if (P->dim == 3 && o->launch == CHERT_LAUNCH_PERSISTENT)
-    return fail(CHERT_ERR_UNSUPPORTED, "3D batches run per-round tiles or the node frontier");
-  P->tiles = P->dim == 3 && o->launch == CHERT_LAUNCH_PER_ROUND;
+  P->tiles = P->dim == 3 &&
+             (o->launch == CHERT_LAUNCH_PER_ROUND || o->launch == CHERT_LAUNCH_PERSISTENT);
   if (P->tiles) {
     if (o->push_group != 0 && o->push_group != 1 && o->push_group != 2 && o->push_group != 4)
       return fail(CHERT_ERR_INVALID_ARG, "push_group must be 0, 1, 2 or 4");
@@ -786,8 +785,8 @@ int trace_batch_frontier(const chert_trace_job* jobs, int n_jobs, const chert_tr
     int rounds = 0;
     rc = relax_tiles_3d(tj.data(), n_jobs, tp.data(), (int)tp.size(), a.ox, a.oy, a.oz, P.n_off,
                         P.R, o->tile_x, o->tile_z, o->push_group, P.max_iter, ws + P.off_tiles,
-                        P.total - P.off_tiles, s, o->abort_flag_host, &rounds, &tile_visits,
-                        &tile_edges);
+                        P.total - P.off_tiles, s, o->abort_flag_host,
+                        o->launch == CHERT_LAUNCH_PERSISTENT, &rounds, &tile_visits, &tile_edges);
     if (rc) return rc;
     iters = rounds;
   }

@@ -20,6 +20,7 @@
 
 #include "chert.h"
 #include "chert_internal.h"
+#include "grid_sync.h"
 
 #pragma clang fp contract(off)
 
@@ -64,7 +65,11 @@ struct T3Args {
   int32_t* list;     // [2][n_tiles] tiles active in a round
   int32_t* counter;  // [max_rounds + 2]
   int32_t* err;
-  unsigned long long* stats;  // [0] visits, [1] edges examined
+  unsigned long long* stats;  // [kStatSlots][16] shards of: [0] visits, [1] edges examined
+  // the caller's abort word (device view of pinned host memory, nullable)
+  // and the device word recording that it was seen (persistent launch)
+  const int32_t* abort_host;
+  int32_t* abort_seen;
 };
 
 __device__ __forceinline__ unsigned long long dbits3(double x) {
@@ -120,7 +125,7 @@ __global__ void k_tile3_clear(int32_t* flags, int64_t n_flags, int32_t* counter,
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t t = tid; t < n_flags; t += (int64_t)gridDim.x * blockDim.x) flags[t] = 0;
   for (int64_t t = tid; t < n_counter; t += (int64_t)gridDim.x * blockDim.x) counter[t] = 0;
-  if (tid == 0) *err = 0;
+  if (tid < 64) err[tid] = 0;  // error word, barrier words, result, abort record
   for (int64_t t = tid; t < kStatSlots * kStatSlotU64; t += (int64_t)gridDim.x * blockDim.x)
     stats[t] = 0ull;
 }
@@ -365,6 +370,42 @@ __global__ void __launch_bounds__(kT3Threads) k_tile3_tau(T3Args a, int round) {
   }
 }
 
+// All rounds in one launch: an occupancy-sized grid walks each round's
+// active list; rounds are separated by the bounded device-wide barrier.
+// The caller's abort word is polled once per round by workgroup 0 and
+// published by the barrier, so every workgroup leaves together.  Result:
+// rounds to convergence, -1 cap reached, -2 barrier timed out, -3 aborted.
+template <int G>
+__global__ void __launch_bounds__(kT3Threads) k_tile3_persist(T3Args a, PersistArgs p) {
+  for (int round = 0; round < p.max_rounds; ++round) {
+    const int n_act =
+        __hip_atomic_load(&a.counter[round], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t* lst = a.list + (int64_t)(round & 1) * a.n_tiles;
+    for (int i = blockIdx.x; i < n_act; i += gridDim.x) {
+      visit3<G>(a, round, lst[i]);
+      __syncthreads();  // LDS is reused by the next tile
+    }
+    if (a.abort_host && blockIdx.x == 0 && threadIdx.x == 0 &&
+        __hip_atomic_load(a.abort_host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
+      __hip_atomic_store(a.abort_seen, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!grid_barrier(p)) {
+      if (threadIdx.x == 0) p.result[0] = -2;
+      return;
+    }
+    if (a.abort_host &&
+        __hip_atomic_load(a.abort_seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) p.result[0] = -3;
+      return;
+    }
+    if (__hip_atomic_load(&a.counter[round + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+        0) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) p.result[0] = round + 1;
+      return;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) p.result[0] = -1;
+}
+
 size_t align256_t3(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct T3Plan {
@@ -417,6 +458,60 @@ int plan_t3(const Tile3Job* jobs, int n_jobs, const Tile3Prob* probs, int n_prob
   return CHERT_OK;
 }
 
+int threads_of(const T3Plan& P) { return (P.tx * P.tx * P.tz + 63) / 64 * 64; }
+
+// Error word and the sharded statistics, after the relaxation (synchronous).
+int read_back(const T3Args& a, hipStream_t s, int32_t* herr, int64_t* visits, int64_t* edges) {
+  unsigned long long hs[2] = {0, 0};
+  std::vector<unsigned long long> slots((size_t)kStatSlots * kStatSlotU64);
+  hipError_t e = hipMemcpyAsync(herr, a.err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(slots.data(), a.stats, kStatBytes, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+  stats_reduce(slots.data(), 2, 0u, hs);
+  *visits = (int64_t)hs[0];
+  *edges = (int64_t)hs[1];
+  return CHERT_OK;
+}
+
+// Every round in one launch of an occupancy-sized grid (all of its
+// workgroups resident, which the device-wide barrier needs).
+int run_persistent(const T3Plan& P, const T3Args& a, int push_group, int max_rounds, int threads,
+                   hipStream_t s, int* rounds, int64_t* visits, int64_t* edges) {
+  void (*kern)(T3Args, PersistArgs) =
+      push_group == 1 ? k_tile3_persist<1> : (push_group == 4 ? k_tile3_persist<4>
+                                                              : k_tile3_persist<2>);
+  int per_cu = 0, cus = 0, dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, P.lds);
+  if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+  if (per_cu < 1) return fail(CHERT_ERR_UNSUPPORTED, "3D tile does not fit on a compute unit");
+  const int64_t resident = (int64_t)per_cu * cus;
+  const int grid = (int)(P.n_tiles < resident ? P.n_tiles : resident);
+  PersistArgs pa{};
+  pa.max_rounds = max_rounds;
+  pa.bar = (uint32_t*)(a.err + 48);     // [0] arrivals, [1] generation, [2] abort
+  pa.result = a.err + 52;
+  CHERT_LAUNCH("k_tile3_clear", k_tile3_clear, dim3(256), dim3(256), 0, s, a.flags,
+               (int64_t)2 * P.n_tiles, a.counter, max_rounds + 2, a.err, a.stats);
+  CHERT_LAUNCH("k_tile3_seed", k_tile3_seed, dim3((a.n_prob + 63) / 64), dim3(64), 0, s, a);
+  CHERT_LAUNCH("k_tile3_persist", kern, dim3((unsigned)grid), dim3((unsigned)threads), P.lds, s,
+               a, pa);
+  int32_t res = 0, herr = 0;
+  e = hipMemcpyAsync(&res, pa.result, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
+  int rc = read_back(a, s, &herr, visits, edges);
+  if (rc) return rc;
+  *rounds = res > 0 ? res : max_rounds;
+  if (res == -3) return fail(CHERT_ERR_ABORTED, "aborted by the caller");
+  if (res == -2) return fail(CHERT_ERR_HIP, "device-wide barrier timed out");
+  if (res <= 0) return fail(CHERT_ERR_NO_CONVERGENCE, "relaxation round cap reached");
+  if (herr) return fail(CHERT_ERR_INVALID_ARG, "class id out of range");
+  return CHERT_OK;
+}
+
 }  // namespace
 
 int tiles3d_bytes(const Tile3Job* jobs, int n_jobs, const Tile3Prob* probs, int n_prob, int R,
@@ -431,7 +526,7 @@ int relax_tiles_3d(const Tile3Job* jobs, int n_jobs, const Tile3Prob* probs, int
                    const int32_t* ox_dev, const int32_t* oy_dev, const int32_t* oz_dev, int n_off,
                    int R, int tile_x, int tile_z, int push_group, int max_rounds, void* ws,
                    size_t ws_bytes, hipStream_t s, const volatile int32_t* abort_flag,
-                   int* rounds, int64_t* visits, int64_t* edges) {
+                   bool persistent, int* rounds, int64_t* visits, int64_t* edges) {
   T3Plan P;
   int rc = plan_t3(jobs, n_jobs, probs, n_prob, R, n_off, tile_x, tile_z, max_rounds, &P);
   if (rc) return rc;
@@ -487,9 +582,23 @@ int relax_tiles_3d(const Tile3Job* jobs, int n_jobs, const Tile3Prob* probs, int
   a.counter = (int32_t*)(w + P.off_counter);
   a.err = (int32_t*)(w + P.off_err);
   a.stats = (unsigned long long*)(w + P.off_stats);
+  a.abort_seen = a.err + 56;
+  a.abort_host = nullptr;
+  if (persistent && abort_flag) {
+    // the persistent grid polls the word itself: page-locked host memory only
+    hipPointerAttribute_t at{};
+    const hipError_t pe = hipPointerGetAttributes(&at, (const void*)abort_flag);
+    if (pe != hipSuccess || at.type != hipMemoryTypeHost || !at.devicePointer) {
+      (void)hipGetLastError();
+      return fail(CHERT_ERR_INVALID_ARG, "abort_flag_host must be pinned host memory");
+    }
+    a.abort_host = (const int32_t*)at.devicePointer;
+  }
+  if (persistent) return run_persistent(P, a, push_group, max_rounds, threads_of(P), s, rounds,
+                                        visits, edges);
   void (*kern)(T3Args, int) = push_group == 1 ? k_tile3_tau<1> : (push_group == 4 ? k_tile3_tau<4>
                                                                                    : k_tile3_tau<2>);
-  const int threads = (P.tx * P.tx * P.tz + 63) / 64 * 64;
+  const int threads = threads_of(P);
   int per_cu = 0, cus = 0, dev = 0;
   e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -521,16 +630,9 @@ int relax_tiles_3d(const Tile3Job* jobs, int n_jobs, const Tile3Prob* probs, int
     }
   }
   int32_t herr = 0;
-  unsigned long long hs[2] = {0, 0};
-  std::vector<unsigned long long> slots((size_t)kStatSlots * kStatSlotU64);
-  e = hipMemcpyAsync(&herr, a.err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(slots.data(), a.stats, kStatBytes, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return fail(CHERT_ERR_HIP, hipGetErrorString(e));
-  stats_reduce(slots.data(), 2, 0u, hs);
+  rc = read_back(a, s, &herr, visits, edges);
+  if (rc) return rc;
   *rounds = done < 0 ? max_rounds : done;
-  *visits = (int64_t)hs[0];
-  *edges = (int64_t)hs[1];
   if (done < 0) return fail(CHERT_ERR_NO_CONVERGENCE, "relaxation round cap reached");
   if (herr) return fail(CHERT_ERR_INVALID_ARG, "class id out of range");
   return CHERT_OK;

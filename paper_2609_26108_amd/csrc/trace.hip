@@ -36,6 +36,7 @@
 
 #include "chert.h"
 #include "chert_internal.h"
+#include "grid_sync.h"
 
 #pragma clang fp contract(off)
 
@@ -1387,53 +1388,6 @@ k_relax_tree(RelaxArgs a, int round) {
 // workgroup that waits longer than kBarrierWaitTicks (or sees another's
 // abort) raises the abort word and leaves, so every wave exits.
 
-constexpr uint64_t kBarrierWaitTicks = 200000000ull;  // 2 s of the 100 MHz real-time clock
-
-struct PersistArgs {
-  int max_rounds;
-  uint32_t* bar;    // [0] arrivals, [1] generation, [2] abort
-  int32_t* result;  // [phase]: rounds to convergence, -1 cap reached, -2 barrier timed out,
-                    // -3 the caller's abort word was raised
-};
-
-// Device-wide barrier; false if aborted.  Release before arriving and
-// acquire after leaving, at agent scope (the L2s of the XCDs are not
-// coherent with each other for plain accesses).
-__device__ __forceinline__ bool grid_barrier(const PersistArgs& p) {
-  __shared__ int s_ok;
-  // every wave's stores have left it; then one agent-scope release (an L2
-  // write-back of this XCD, which covers every wave of the workgroup)
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    int ok = 1;
-    const uint32_t gen =
-        __hip_atomic_load(&p.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t arrived =
-        __hip_atomic_fetch_add(&p.bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == gridDim.x - 1) {
-      __hip_atomic_store(&p.bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&p.bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      const uint64_t t0 = wall_clock64();
-      while (__hip_atomic_load(&p.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        if (__hip_atomic_load(&p.bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-            wall_clock64() - t0 > kBarrierWaitTicks) {
-          ok = 0;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
-      }
-    }
-    if (!ok) __hip_atomic_store(&p.bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s_ok = ok;
-    __threadfence();  // acquire: invalidates this CU's L1 and this XCD's L2
-  }
-  __syncthreads();
-  return s_ok != 0;
-}
-
 template <int G, int PH>
 __global__ void __launch_bounds__(kRelaxThreads) k_relax_persist(RelaxArgs a, PersistArgs p) {
   for (int round = 0; round < p.max_rounds; ++round) {
@@ -2267,17 +2221,18 @@ extern "C" int chert_trace_autotune(const chert_trace_job* jobs, int32_t n_jobs,
     c.bucket_width = bws[q];
     cands.push_back(c);
   }
-  if (three_d)  // 3D tiles (tile_x x tile_x x tile_z), per-round launches
+  if (three_d)  // 3D tiles (tile_x x tile_x x tile_z), per-round or persistent
     for (const auto& t : kTuneTiles3D)
-      for (int G : kTuneGroups) {
-        chert_trace_opts c = *o;
-        c.tile_x = t[0];
-        c.tile_z = t[1];
-        c.push_group = G;
-        c.launch = CHERT_LAUNCH_PER_ROUND;
-        c.bucket_width = 0.0;
-        cands.push_back(c);
-      }
+      for (int G : kTuneGroups)
+        for (int L : kTuneLaunch) {
+          chert_trace_opts c = *o;
+          c.tile_x = t[0];
+          c.tile_z = t[1];
+          c.push_group = G;
+          c.launch = L;
+          c.bucket_width = 0.0;
+          cands.push_back(c);
+        }
   if (!three_d)
     for (const auto& t : kTuneTiles)
       for (int G : kTuneGroups2D)
@@ -2317,8 +2272,9 @@ extern "C" int chert_trace_autotune(const chert_trace_job* jobs, int32_t n_jobs,
     }
   };
   for (const chert_trace_opts& c : cands) consider(c);
-  // tiles: then the ordering width for the fastest shape
-  if (tried > 0 && pick.launch != CHERT_LAUNCH_FRONTIER)
+  // 2D tiles: then the ordering width for the fastest shape (the 3D tiles
+  // have no ordering)
+  if (tried > 0 && pick.launch != CHERT_LAUNCH_FRONTIER && !three_d)
     for (double bw : kTuneTileBuckets) {
       chert_trace_opts c = pick;
       c.bucket_width = bw;

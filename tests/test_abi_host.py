@@ -200,10 +200,12 @@ def test_device_calls_validate_before_launch():
     assert C.chert_trace_workspace_bytes(d3, 3, g3, 1, o3) > 0
     g3b = C.Grid(3, 5, 10, 10, 10, 5.0, 5.0, 5.0, 1234)
     assert C.chert_trace_workspace_bytes(d3, 3, g3b, 1, o3) == 0  # radius above 4
-    # 3D: per-round tiles (tile_x x tile_x x tile_z) or the node frontier
-    of3 = C.trace_opts(C.OUT_TAU_R | C.OUT_TAU_I, launch=C.LAUNCH_FRONTIER)
-    assert C.chert_trace_workspace_bytes(d3, 3, g3, 1, of3) > 0
-    for bad in (dict(launch=C.LAUNCH_PERSISTENT), dict(tile_x=2, tile_z=8),
+    # 3D: tiles (tile_x x tile_x x tile_z, per round or persistent) or the
+    # node frontier
+    for launch in (C.LAUNCH_FRONTIER, C.LAUNCH_PERSISTENT):
+        of3 = C.trace_opts(C.OUT_TAU_R | C.OUT_TAU_I, launch=launch)
+        assert C.chert_trace_workspace_bytes(d3, 3, g3, 1, of3) > 0
+    for bad in (dict(tile_x=2, tile_z=8),
                 dict(tile_x=16, tile_z=8), dict(push_group=3)):
         ob = C.trace_opts(C.OUT_TAU_R | C.OUT_TAU_I, **bad)
         assert C.chert_trace_workspace_bytes(d3, 3, g3, 1, ob) == 0, bad

@@ -97,9 +97,11 @@ def small3d():
     return m, cls, f, s
 
 
-def trace3(G, m, cache, desc, K, mode, bucket=0.0, full=False, launch=2, tile=(0, 0), group=0):
+def trace3(G, m, cache, desc, K, mode, bucket=0.0, full=False, launch=2, tile=(0, 0), group=0,
+           abort=None):
     """tau_R, tau_I (and with full=True also t*, pred_P, pred_A) of every
-    source; launch 2 = node frontier, 0 = 3D tiles (tile_x, tile_z); returns
+    source; launch 2 = node frontier, 0 = 3D tiles (tile_x, tile_z) one
+    launch per round, 1 = the same tiles in one persistent launch; returns
     numpy arrays and the counters."""
     Cm = C()
     cid = torch.from_numpy(np.ascontiguousarray(m.class_id.reshape(-1), dtype=np.int32)).to(G.DEV)
@@ -107,7 +109,7 @@ def trace3(G, m, cache, desc, K, mode, bucket=0.0, full=False, launch=2, tile=(0
     stats = Cm.TraceStats()
     outs = Cm.OUT_ALL if full else Cm.OUT_TAU_R | Cm.OUT_TAU_I
     o = Cm.trace_opts(outs, tile[0], tile[1], stats=stats, bucket_width=bucket, launch=launch,
-                      push_group=group)
+                      push_group=group, abort_flag=abort)
     S, n = len(m.sources), m.n_nodes
     tr = torch.empty((S, n), dtype=torch.float64, device=G.DEV)
     ti = torch.empty((S, n), dtype=torch.float64, device=G.DEV)
@@ -126,12 +128,14 @@ def trace3(G, m, cache, desc, K, mode, bucket=0.0, full=False, launch=2, tile=(0
 
 @pytest.mark.parametrize("launch,bucket,tile,group", [
     (2, 0.0, (0, 0), 0), (2, 3.0, (0, 0), 0), (2, 16.0, (0, 0), 0),
-    (0, 0.0, (0, 0), 0), (0, 0.0, (4, 16), 1), (0, 0.0, (16, 4), 4), (0, 0.0, (3, 3), 2)])
+    (0, 0.0, (0, 0), 0), (0, 0.0, (4, 16), 1), (0, 0.0, (16, 4), 4), (0, 0.0, (3, 3), 2),
+    (1, 0.0, (0, 0), 0), (1, 0.0, (4, 16), 1), (1, 0.0, (3, 3), 4)])
 def test_trace_3d_imported_cache_bitwise(G, small3d, launch, bucket, tile, group):
     """On the oracle's cache, every 3D traveltime (three sources, two modes,
     tau_R and tau_I) equals the oracle's Dijkstra bitwise: on the node
     frontier with one bucket or near/far buckets of several widths, and on
-    3D tiles of several shapes (ragged at the grid's far faces)."""
+    3D tiles of several shapes (ragged at the grid's far faces), launched
+    per round or persistently."""
     Cm = C()
     m, cls, f, s = small3d
     K = cls.shape[0]
@@ -148,7 +152,7 @@ def test_trace_3d_imported_cache_bitwise(G, small3d, launch, bucket, tile, group
             assert np.array_equal(ti[si], o["tauI"]), (mode, si)
 
 
-@pytest.mark.parametrize("launch,bucket", [(2, 0.0), (2, 16.0), (0, 0.0)])
+@pytest.mark.parametrize("launch,bucket", [(2, 0.0), (2, 16.0), (0, 0.0), (1, 0.0)])
 def test_trace_3d_predecessors_and_tstar_bitwise(G, small3d, launch, bucket):
     """Predecessors of both fields (BFS hop over tight edges, then the
     smallest offset index) and t* along the propagation tree equal the
@@ -169,7 +173,7 @@ def test_trace_3d_predecessors_and_tstar_bitwise(G, small3d, launch, bucket):
                                                             int(np.sum(g[key][si] != o[key])))
 
 
-@pytest.mark.parametrize("launch", [0, 2])
+@pytest.mark.parametrize("launch", [0, 1, 2])
 def test_trace_3d_end_to_end(G, small3d, launch):
     """GPU cache -> GPU 3D trace (tiles or frontier) against oracle cache ->
     oracle Dijkstra: 1e-9 relative."""
@@ -189,7 +193,7 @@ def test_trace_3d_end_to_end(G, small3d, launch):
             assert rel.max() <= 1e-9, rel.max()
 
 
-@pytest.mark.parametrize("launch", [0, 2])
+@pytest.mark.parametrize("launch", [0, 1, 2])
 def test_trace_3d_invalid_class_id_reported(G, small3d, launch):
     Cm = C()
     m, cls, f, s = small3d
@@ -202,6 +206,54 @@ def test_trace_3d_invalid_class_id_reported(G, small3d, launch):
     with pytest.raises(Cm.ChertError) as e:
         trace3(G, m2, cache, desc, K, 0, launch=launch)
     assert e.value.code == 1
+
+
+def _abort_word(value):
+    w = torch.zeros(1, dtype=torch.int32).pin_memory()
+    w[0] = value
+    return w
+
+
+@pytest.mark.parametrize("launch", [0, 1, 2])
+def test_trace_3d_abort_word(G, small3d, launch):
+    """A raised abort word stops a 3D trace at a round boundary (tiles per
+    round: host check; persistent tiles: workgroup 0 polls it before the
+    device-wide barrier; frontier: host check):
+    the call returns ABORTED; a word that stays 0 changes nothing."""
+    Cm = C()
+    m, cls, f, s = small3d
+    K = cls.shape[0]
+    desc = Cm.cache_desc(dim=3, n_dirs=400, modes=(0, 1), n_sweep=360)
+    cache = G.import_cache(f, s, desc, K)
+    ref = [O.trace_3d(m.nx, m.ny, m.nz, m.h, m.h, m.h, m.class_id, m.radius, f[0, 0], f[1, 0],
+                      s[0], src, N=400) for src in m.sources]
+    tile = (3, 3) if launch != 2 else (0, 0)  # small tiles: many rounds
+    word = _abort_word(0)
+    tr, ti, st = trace3(G, m, cache, desc, K, 0, launch=launch, tile=tile, abort=word)
+    for si in range(len(m.sources)):
+        assert np.array_equal(tr[si], ref[si]["tauR"]) and np.array_equal(ti[si], ref[si]["tauI"])
+    print("rounds", st["rounds"])
+    word[0] = 1
+    # the per-round tiles look at the word after each group of 8 rounds
+    if launch == 0 and st["rounds"][0] <= 8:
+        return
+    with pytest.raises(Cm.ChertError) as e:
+        trace3(G, m, cache, desc, K, 0, launch=launch, tile=tile, abort=word)
+    assert e.value.code == Cm.ERR_ABORTED, e.value
+
+
+def test_trace_3d_persistent_needs_pinned_abort_word(G, small3d):
+    """The persistent 3D launch polls the abort word from the device: a word
+    in pageable host memory is refused (INVALID_ARG) before any relaxation."""
+    Cm = C()
+    m, cls, f, s = small3d
+    K = cls.shape[0]
+    desc = Cm.cache_desc(dim=3, n_dirs=400, modes=(0, 1), n_sweep=360)
+    cache = G.import_cache(f, s, desc, K)
+    word = torch.zeros(1, dtype=torch.int32)
+    with pytest.raises(Cm.ChertError) as e:
+        trace3(G, m, cache, desc, K, 0, launch=1, abort=word)
+    assert e.value.code == Cm.ERR_INVALID_ARG, e.value
 
 
 def test_trace_3d_autotuned_bucket(G, small3d):
@@ -225,8 +277,8 @@ def test_trace_3d_autotuned_bucket(G, small3d):
     if o.launch == Cm.LAUNCH_FRONTIER:
         assert o.bucket_width in (0.0, 4.0, 16.0, 32.0, 64.0, 128.0, 256.0)
     else:
-        assert o.launch == Cm.LAUNCH_PER_ROUND and (o.tile_x, o.tile_z) in (
-            (8, 8), (8, 16), (16, 4), (4, 16))
+        assert o.launch in (Cm.LAUNCH_PER_ROUND, Cm.LAUNCH_PERSISTENT)
+        assert (o.tile_x, o.tile_z) in ((8, 8), (8, 16), (16, 4), (4, 16))
     tr.fill_(-1.0)
     Cm.chert_trace_batch(b, o, ws)
     torch.cuda.synchronize()
