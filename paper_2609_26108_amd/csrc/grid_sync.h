@@ -14,10 +14,25 @@ constexpr uint64_t kBarrierWaitTicks = 200000000ull;  // 2 s of the 100 MHz real
 
 struct PersistArgs {
   int max_rounds;
-  uint32_t* bar;    // [0] arrivals, [1] generation, [2] abort
+  uint32_t* bar;    // [0] arrivals, [1] generation, [2] abort, [3] work tickets
   int32_t* result;  // [phase]: rounds to convergence, -1 cap reached, -2 barrier timed out,
                     // -3 the caller's abort word was raised
 };
+
+// Dynamic hand-out of a round's n_act list entries to the persistent grid:
+// each workgroup draws tickets from one counter that is never reset.  A
+// round issues exactly n_act + gridDim.x tickets (every workgroup stops at
+// its first ticket past the list), so all workgroups advance `base` alike;
+// the differences are taken modulo 2^32.  Returns the next entry, or -1.
+__device__ __forceinline__ int next_item(const PersistArgs& p, uint32_t base, int n_act) {
+  __shared__ uint32_t s_ticket;
+  if (threadIdx.x == 0)
+    s_ticket = __hip_atomic_fetch_add(&p.bar[3], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const uint32_t d = s_ticket - base;
+  __syncthreads();  // every thread has read the ticket before the next draw
+  return d < (uint32_t)n_act ? (int)d : -1;
+}
 
 // Device-wide barrier; false if aborted.  Release before arriving and
 // acquire after leaving, at agent scope (the L2s of the XCDs are not

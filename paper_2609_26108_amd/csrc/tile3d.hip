@@ -377,14 +377,16 @@ __global__ void __launch_bounds__(kT3Threads) k_tile3_tau(T3Args a, int round) {
 // rounds to convergence, -1 cap reached, -2 barrier timed out, -3 aborted.
 template <int G>
 __global__ void __launch_bounds__(kT3Threads) k_tile3_persist(T3Args a, PersistArgs p) {
+  uint32_t base = 0;  // work tickets issued before this round
   for (int round = 0; round < p.max_rounds; ++round) {
     const int n_act =
         __hip_atomic_load(&a.counter[round], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int32_t* lst = a.list + (int64_t)(round & 1) * a.n_tiles;
-    for (int i = blockIdx.x; i < n_act; i += gridDim.x) {
+    for (int i = next_item(p, base, n_act); i >= 0; i = next_item(p, base, n_act)) {
       visit3<G>(a, round, lst[i]);
       __syncthreads();  // LDS is reused by the next tile
     }
+    base += (uint32_t)n_act + gridDim.x;
     if (a.abort_host && blockIdx.x == 0 && threadIdx.x == 0 &&
         __hip_atomic_load(a.abort_host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
       __hip_atomic_store(a.abort_seen, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -492,7 +494,7 @@ int run_persistent(const T3Plan& P, const T3Args& a, int push_group, int max_rou
   const int grid = (int)(P.n_tiles < resident ? P.n_tiles : resident);
   PersistArgs pa{};
   pa.max_rounds = max_rounds;
-  pa.bar = (uint32_t*)(a.err + 48);     // [0] arrivals, [1] generation, [2] abort
+  pa.bar = (uint32_t*)(a.err + 48);  // [0] arrivals, [1] generation, [2] abort, [3] tickets
   pa.result = a.err + 52;
   CHERT_LAUNCH("k_tile3_clear", k_tile3_clear, dim3(256), dim3(256), 0, s, a.flags,
                (int64_t)2 * P.n_tiles, a.counter, max_rounds + 2, a.err, a.stats);

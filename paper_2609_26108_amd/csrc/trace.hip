@@ -371,7 +371,7 @@ __global__ void k_clear_flags(int32_t* flags, int64_t n_flags, int32_t* counter,
   for (int64_t t = tid; t < n_counter; t += (int64_t)gridDim.x * blockDim.x) counter[t] = 0;
   for (int64_t t = tid; t < n_key; t += (int64_t)gridDim.x * blockDim.x) key[t] = kInfBits;
   for (int64_t t = tid; t < n_pmin; t += (int64_t)gridDim.x * blockDim.x) pmin[t] = kInfBits;
-  if (tid < 3) bar[tid] = 0u;  // barrier arrivals, generation, abort
+  if (tid < 4) bar[tid] = 0u;  // barrier arrivals, generation, abort, work tickets
 }
 
 // activate the source tile of every problem (tree phase: only problems
@@ -1390,17 +1390,21 @@ k_relax_tree(RelaxArgs a, int round) {
 
 template <int G, int PH>
 __global__ void __launch_bounds__(kRelaxThreads) k_relax_persist(RelaxArgs a, PersistArgs p) {
+  uint32_t base = 0;  // work tickets issued before this round
   for (int round = 0; round < p.max_rounds; ++round) {
     if (blockIdx.x == 0) reset_pmin(a, round);
     const int n_act =
         __hip_atomic_load(&a.counter[round], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int32_t* lst = a.list + (int64_t)(round & 1) * a.n_tiles;
-    for (int i = blockIdx.x; i < n_act; i += gridDim.x) {
+    // visits differ in length by tens of levels: tiles are handed out as
+    // workgroups free up rather than dealt round-robin
+    for (int i = next_item(p, base, n_act); i >= 0; i = next_item(p, base, n_act)) {
       const int T = lst[i];
       if constexpr (PH == 0) relax_tau<G>(a, round, T);
       else relax_tree(a, round, T);
       __syncthreads();  // LDS is reused by the next tile
     }
+    base += (uint32_t)n_act + gridDim.x;
     // the caller's abort word, polled once per round by workgroup 0 and
     // published by the barrier below, so every workgroup leaves together
     if (a.abort_host && blockIdx.x == 0 && threadIdx.x == 0 && host_abort(a))
