@@ -542,16 +542,18 @@ __device__ __forceinline__ void mark_window(const SolveArgs& a, const double* ps
 // mark ray-angle bins where the map may have several branches.  All 64 lanes;
 // s_fold and *s_all must be cleared (and a barrier passed) before the call;
 // ends with a barrier.
-__device__ __forceinline__ void proxy_folds(const Medium& me, int mode, int kernel, double* s_psi,
-                                            uint32_t* s_fold, int* s_all) {
-  const int lane = threadIdx.x;
-  for (int j = lane; j < kProxyN; j += 64) {
+// `work`: this lane takes part, as lane l of the L serving this job; every
+// thread of the workgroup calls it (it holds two workgroup barriers)
+__device__ __forceinline__ void proxy_folds(const Medium& me, int mode, int kernel, bool work,
+                                            int l, int L, double* s_psi, uint32_t* s_fold,
+                                            int* s_all) {
+  for (int j = l; work && j < kProxyN; j += L) {
     double sr, cr;  // real angle: sinh 0 = 0, cosh 0 = 1
     sincos((j + 0.5) * (kPi / kProxyN), &sr, &cr);
     s_psi[j] = ray_angle(energy_velocity_t(me, mode, kernel, Trig{sr, cr, 0.0, 1.0}));
   }
   __syncthreads();
-  for (int j = lane; j < kProxyN; j += 64) {
+  for (int j = l; work && j < kProxyN; j += L) {
     const double pa = s_psi[j];
     const double pb = j + 1 < kProxyN ? s_psi[j + 1] : s_psi[0] + kPi;
     if (!isfinite(pa) || !isfinite(pb)) {
@@ -581,61 +583,76 @@ __device__ __forceinline__ Medium elastic_of(const Medium& m) {
   return me;
 }
 
-// One wavefront per (mode, class) job: every direction away from a fold is
-// polished from its prediction.  A job with a rejected direction goes to the
-// plain path (fb_list); a job whose other directions all passed and that has
-// directions near a fold goes to k_warm_window (win_list).  Small static LDS
-// only, so occupancy is set by registers.
-__global__ void __launch_bounds__(64) k_warm_solve(WarmArgs w) {
-  __shared__ double s_psi[kProxyN];
-  __shared__ uint32_t s_fold[kFoldWords];
+// Several (mode, class) jobs per workgroup, L = min(n_solve, 64) lanes each
+// (one lane per solved direction; with n_solve = 40 a job per wavefront
+// left 24 lanes idle): every direction away from a fold is polished from
+// its prediction.  A job with a rejected direction goes to the plain path
+// (fb_list); a job whose other directions all passed and that has
+// directions near a fold goes to k_warm_window (win_list).  Small static
+// LDS only, so occupancy is set by registers.
+constexpr int kWarmSolveThreads = 256;
+constexpr int kWarmSolveJobs = 16;  // most jobs a workgroup holds
+__host__ __device__ inline int warm_lanes(int n_solve) { return n_solve < 64 ? n_solve : 64; }
+__host__ __device__ inline int warm_jobs(int n_solve) {
+  const int j = kWarmSolveThreads / warm_lanes(n_solve);
+  return j < kWarmSolveJobs ? j : kWarmSolveJobs;
+}
+
+__global__ void __launch_bounds__(kWarmSolveThreads) k_warm_solve(WarmArgs w, int64_t n_jobs) {
+  __shared__ double s_psi[kWarmSolveJobs][kProxyN];
+  __shared__ uint32_t s_fold[kWarmSolveJobs][kFoldWords];
+  __shared__ int s_all[kWarmSolveJobs], s_nflag[kWarmSolveJobs], s_rej[kWarmSolveJobs];
   __shared__ uint32_t s_cnt[CHERT_WARM_NSTATS];
-  __shared__ int s_all, s_nflag;
 
   const SolveArgs& a = w.so;
-  const int64_t job = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int64_t k = job % a.n_classes;
-  const int mode = a.modes[job / a.n_classes];
+  const int L = warm_lanes(a.n_solve), J = warm_jobs(a.n_solve);
+  const int q = (int)threadIdx.x / L, l = (int)threadIdx.x % L;
+  const int64_t job = (int64_t)blockIdx.x * J + q;
+  const bool on = q < J && job < n_jobs;  // this lane serves a job
+  const int qs = q < J ? q : 0;           // its LDS slot (idle lanes: any)
+  for (int i = threadIdx.x; i < CHERT_WARM_NSTATS; i += blockDim.x) s_cnt[i] = 0;
+  for (int i = threadIdx.x; i < kWarmSolveJobs * kFoldWords; i += blockDim.x)
+    (&s_fold[0][0])[i] = 0;
+  if (threadIdx.x < kWarmSolveJobs) {
+    s_all[threadIdx.x] = 0;
+    s_nflag[threadIdx.x] = 0;
+    s_rej[threadIdx.x] = 0;
+  }
+  const int64_t k = on ? job % a.n_classes : 0;
+  const int mode = on ? a.modes[job / a.n_classes] : 0;
   const chert_class c = a.classes[k];
   const int64_t row = ((int64_t)mode * a.n_classes + k) * a.n_cols;
-  if (lane < CHERT_WARM_NSTATS) s_cnt[lane] = 0;
-  if (lane < kFoldWords) s_fold[lane] = 0;
-  if (lane == 0) {
-    s_all = 0;
-    s_nflag = 0;
-  }
-  const int32_t blocked = class_block(c, mode);
-  if (blocked) {
+  const int32_t blocked = on ? class_block(c, mode) : 0;
+  const bool work = on && !blocked;
+  __syncthreads();  // LDS cleared
+  if (on && l == 0) atomicAdd(&s_cnt[0], 1u);
+  if (on && blocked) {
     Entry none{};
     none.V = NAN;
-    for (int sidx = lane; sidx < a.n_solve; sidx += 64) {
+    for (int sidx = l; sidx < a.n_solve; sidx += L) {
       int d, col, pcol;
       dir_cols(a, sidx, &d, &col, &pcol);
       store_pair(a, row, col, pcol, none, 0.0, blocked);
     }
-    if (lane == 0) atomicAdd(&stat_slot(w.shard)[0], 1ull);
-    return;  // block-uniform
   }
   const Medium m = load_medium(c);
   const bool el = theta_i_zero(m, mode);
-  __syncthreads();
-  proxy_folds(elastic_of(m), mode, a.kernel, s_psi, s_fold, &s_all);
+  proxy_folds(elastic_of(m), mode, a.kernel, work, l, L, s_psi[qs], s_fold[qs], &s_all[qs]);
 
   bool reject = false;
-  for (int sidx = lane; sidx < a.n_solve; sidx += 64) {
+  for (int sidx = l; work && sidx < a.n_solve; sidx += L) {
     int d, col, pcol;
     dir_cols(a, sidx, &d, &col, &pcol);
     const double psi_star = dir_psi(a, d, m.tilt);
     atomicAdd(&s_cnt[2], 1u);
     const int fb = fold_bin(psi_star);
-    if (s_all) {
+    if (s_all[qs]) {
       reject = true;
       continue;
     }
-    if ((s_fold[fb >> 5] >> (fb & 31)) & 1u) {  // near a fold: k_warm_window
+    if ((s_fold[qs][fb >> 5] >> (fb & 31)) & 1u) {  // near a fold: k_warm_window
       atomicAdd(&s_cnt[3], 1u);
-      atomicAdd(&s_nflag, 1);
+      atomicAdd(&s_nflag[qs], 1);
       continue;
     }
     const float2 p = w.pred[job * a.n_solve + sidx];
@@ -672,19 +689,19 @@ __global__ void __launch_bounds__(64) k_warm_solve(WarmArgs w) {
     }
     store_pair(a, row, col, pcol, e, m.tilt, CHERT_ST_OK);
   }
-  const bool any = __any(reject);
+  if (reject) s_rej[qs] = 1;
   __syncthreads();
-  if (lane == 0) {
-    s_cnt[0] = 1;
-    if (any) {
-      s_cnt[1] = 1;
+  if (work && l == 0) {
+    if (s_rej[qs]) {
+      atomicAdd(&s_cnt[1], 1u);
       w.fb_list[atomicAdd(w.fb_len, 1)] = (int32_t)job;
-    } else if (s_nflag > 0) {
+    } else if (s_nflag[qs] > 0) {
       w.win_list[atomicAdd(w.win_len, 1)] = (int32_t)job;
     }
   }
   __syncthreads();
-  if (lane < CHERT_WARM_NSTATS && s_cnt[lane]) atomicAdd(&stat_slot(w.shard)[lane], (unsigned long long)s_cnt[lane]);
+  for (int i = threadIdx.x; i < CHERT_WARM_NSTATS; i += blockDim.x)
+    if (s_cnt[i]) atomicAdd(&stat_slot(w.shard)[i], (unsigned long long)s_cnt[i]);
 }
 
 // Directions near a fold, for the jobs k_warm_solve listed: the plain
@@ -731,7 +748,7 @@ __global__ void __launch_bounds__(64) k_warm_window(WarmArgs w) {
     for (int i = lane; i < a.n_sweep; i += 64) s_pos[i] = -1;
     for (int i = lane; i < n_words; i += 64) s_mask[i] = 0u;
     __syncthreads();
-    proxy_folds(me, mode, a.kernel, s_psi, s_fold, &s_all);
+    proxy_folds(me, mode, a.kernel, true, lane, 64, s_psi, s_fold, &s_all);
     for (int sidx = lane; sidx < a.n_solve; sidx += 64) {
       int d, col, pcol;
       dir_cols(a, sidx, &d, &col, &pcol);
@@ -983,8 +1000,8 @@ __global__ void __launch_bounds__(64) k_warm3_folds(Warm3Args w) {
   if (threadIdx.x < kFoldWords) s_fold[threadIdx.x] = 0u;
   if (threadIdx.x == 0) s_all = 0;
   __syncthreads();
-  if (!class_block(c, mode)) proxy_folds(elastic_of(load_medium(c)), mode, a.kernel, s_psi, s_fold,
-                                         &s_all);
+  proxy_folds(elastic_of(load_medium(c)), mode, a.kernel, !class_block(c, mode), threadIdx.x, 64,
+              s_psi, s_fold, &s_all);
   __syncthreads();
   if (threadIdx.x < kFoldWords)
     w.fold[job * kFoldWords + threadIdx.x] = s_all ? ~0u : s_fold[threadIdx.x];
@@ -1565,7 +1582,9 @@ extern "C" int chert_build_cache_surrogate(const chert_cache_desc* d,
     if (blocks > 0x7fffffffLL) return fail(CHERT_ERR_INVALID_ARG, "too many entries");
     CHERT_LAUNCH("k_warm_predict", k_warm_predict, dim3((unsigned)blocks), dim3(mlp::kThreads),
                  0, s, w, rows);
-    CHERT_LAUNCH("k_warm_solve", k_warm_solve, dim3((unsigned)jobs), dim3(64), 0, s, w);
+    const int per = warm_jobs(w.so.n_solve);
+    CHERT_LAUNCH("k_warm_solve", k_warm_solve, dim3((unsigned)((jobs + per - 1) / per)),
+                 dim3(kWarmSolveThreads), 0, s, w, jobs);
     const int64_t grid = jobs < 4096 ? jobs : 4096;
     CHERT_LAUNCH("k_warm_window", k_warm_window, dim3((unsigned)grid), dim3(64),
                  kWinCap * (sizeof(double2) + sizeof(int16_t)) +
