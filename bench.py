@@ -52,13 +52,13 @@ FP64_VALU_PEAK_TOPS = 39.3  # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz, one o
 # Valid only for the kernel source it was measured on.
 MEASURED_TRAFFIC = {
     "source": "paper_2609_26108_amd/csrc/trace.hip",
-    "source_sha256_16": "953ac49953088a6b",
+    "source_sha256_16": "4292a0880d303c09",
     "fetch_scale": 2.0, "write_scale": 1.0,
     # workload -> kernel -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
     # (profiles/k_relax_tau__shots_4_grids_per_node.md: one step, 16 x 64
     # tiles, push group 4, 112 dispatches of each relaxation kernel)
-    "kib_per_dispatch": {"shots": {"k_relax_tau": (789838.42, 10509.06),
-                                   "k_relax_tree": (256364.75, 40187.29)}},
+    "kib_per_dispatch": {"shots": {"k_relax_tau": (786200.60, 10522.81),
+                                   "k_relax_tree": (257375.12, 40202.05)}},
 }
 
 
@@ -84,8 +84,8 @@ def measured_traffic_bytes(kernel, workload="layered"):
 MEASURED_FP64 = {
     "sources": ["paper_2609_26108_amd/csrc/cache_build.hip",
                 "paper_2609_26108_amd/csrc/physics.h", "paper_2609_26108_amd/csrc/mlp.h"],
-    "sources_sha256_16": "db564de836b3570d",
-    "flops_per_dispatch": {"k_warm_solve": 4.9490e11, "k_warm_window": 2.8714e11,
+    "sources_sha256_16": "7829c908b494a563",
+    "flops_per_dispatch": {"k_warm_solve": 3.7921e11, "k_warm_window": 2.8714e11,
                            "k_warm_fold": 2.1870e10, "k_warm_predict": 5.3496e9},
 }
 
