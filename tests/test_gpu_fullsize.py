@@ -160,6 +160,29 @@ def shots(G):
     for (_, _, out), ref in zip(keep, eager_out):
         for k, v in out.items():
             assert torch.equal(v, ref[k]), k
+    # the persistent launch (tickets drawn per round) and its graph give the
+    # same fields as the per-round launches
+    popts = C.trace_opts(outs, opts.tile_x, opts.tile_z, push_group=opts.push_group,
+                         launch=C.LAUNCH_PERSISTENT, bucket_width=opts.bucket_width)
+    assert C.chert_trace_batch_workspace_bytes(b, popts) <= ws.numel()
+    for use_graph in (False, True):
+        for _, _, out in keep:
+            for t in out.values():
+                t.fill_(-9)
+        torch.cuda.synchronize()
+        if use_graph:
+            with torch.cuda.stream(stream):
+                graph = C.TraceGraph(b, popts, ws, stream=stream)
+                graph.launch(stream)
+                graph.finish(None, stream)
+            graph.close()
+        else:
+            C.chert_trace_batch(b, popts, ws)
+        torch.cuda.synchronize()
+        for (_, _, out), ref in zip(keep, eager_out):
+            for k, v in out.items():
+                assert torch.equal(v, ref[k]), ("persistent", use_graph, k)
+        print("persistent launch equal, graph", use_graph, flush=True)
     del eager_out
     return caches, keep
 
