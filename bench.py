@@ -871,6 +871,29 @@ def run_shots(args):
             finally:
                 graph.close()
 
+    # the persistent form of the same batch (one launch per phase with the
+    # device-wide barrier between rounds) as a graph replay, for comparison
+    pgraph_s = None
+    if opts.launch in (C.LAUNCH_PER_ROUND, C.LAUNCH_PERSISTENT):
+        popts = C.trace_opts(outs_mask, opts.tile_x, opts.tile_z, push_group=opts.push_group,
+                             launch=C.LAUNCH_PERSISTENT, bucket_width=opts.bucket_width)
+        if C.chert_trace_batch_workspace_bytes(b_warm, popts) <= tws.numel():
+            gs = torch.cuda.Stream()
+            torch.cuda.synchronize()
+            with torch.cuda.stream(gs):
+                graph = C.TraceGraph(b_warm, popts, tws, stream=gs)
+                try:
+                    graph.launch(gs)
+                    graph.finish(None, gs)
+                    e0 = _events(torch, gs)
+                    reps = 3
+                    for _ in range(reps):
+                        graph.launch(gs)
+                    graph.finish(None, gs)
+                    pgraph_s = _elapsed(torch, e0, gs) / reps
+                finally:
+                    graph.close()
+
     # plain per-node build of every grid (timed once, after one warm-up grid)
     C.chert_build_cache(grids[0]["desc"], grids[0]["cls"], grids[0]["n"], grids[0]["plain"],
                         None, stream=stream)
@@ -945,6 +968,8 @@ def run_shots(args):
             "shots_per_s_trace_only": shots / (trace_ms * 1e-3),
             "graph_replay_trace_s": graph_s,
             "shots_per_s_graph_trace_only": shots / graph_s if graph_s else None,
+            "persistent_graph_replay_trace_s": pgraph_s,
+            "shots_per_s_persistent_graph_trace_only": shots / pgraph_s if pgraph_s else None,
             "tau_R_rel_surrogate_vs_plain_max": worst, "tau_R_within_1e-4": worst <= 1e-4,
             "same_reachability": same_reach, "warm_status_equals_plain": same_status,
             "warm_stats": wstats, "training": tinfo, "build_opcount": opc,
