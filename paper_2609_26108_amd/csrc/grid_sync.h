@@ -12,26 +12,82 @@ namespace chert {
 
 constexpr uint64_t kBarrierWaitTicks = 200000000ull;  // 2 s of the 100 MHz real-time clock
 
+// Work-ticket counters of the persistent launches: one 128-byte line per
+// shard, so that draws spread over several addresses (atomics on one
+// address serialise across the chip).
+constexpr int kTickShards = 8;
+constexpr int kTickStride = 32;  // 32-bit words between shards
+constexpr int kTickWords = kTickShards * kTickStride;
+
+// Round counters of a launch: [max_rounds + 2] list lengths, padded to a
+// 128-byte line, then the ticket counters (all zeroed together).
+__host__ __device__ inline size_t tick_offset(int max_rounds) {
+  return ((size_t)max_rounds + 2 + 31) / 32 * 32;
+}
+__host__ __device__ inline size_t counter_words(int max_rounds) {
+  return tick_offset(max_rounds) + 2 * kTickWords;  // per-round launches: by round parity
+}
+
 struct PersistArgs {
   int max_rounds;
-  uint32_t* bar;    // [0] arrivals, [1] generation, [2] abort, [3] work tickets
+  uint32_t* bar;    // [0] arrivals, [1] generation, [2] abort
   int32_t* result;  // [phase]: rounds to convergence, -1 cap reached, -2 barrier timed out,
                     // -3 the caller's abort word was raised
+  uint32_t* tick;   // [kTickWords] zeroed before the launch, never reset during it
 };
 
-// Dynamic hand-out of a round's n_act list entries to the persistent grid:
-// each workgroup draws tickets from one counter that is never reset.  A
-// round issues exactly n_act + gridDim.x tickets (every workgroup stops at
-// its first ticket past the list), so all workgroups advance `base` alike;
-// the differences are taken modulo 2^32.  Returns the next entry, or -1.
-__device__ __forceinline__ int next_item(const PersistArgs& p, uint32_t base, int n_act) {
+// Dynamic hand-out of a round's n_act list entries to the persistent grid.
+// The entries and workgroups are split into S = min(kTickShards, gridDim.x)
+// shards by index mod S.  Within its shard a workgroup of rank r takes entry
+// r first (no atomic, so a round does not start with every workgroup
+// queueing on one address); when the shard has more entries than
+// workgroups, each draws one ticket per entry it visits from the shard's
+// counter for the remaining ones, and stops at its first ticket past them.
+// Such a shard issues exactly as many tickets per round as it has entries,
+// a shorter one none; the counters are never reset, so every workgroup
+// advances its shard's `base` alike (round_tickets), differences taken
+// modulo 2^32.
+struct Shard {
+  int s, S, rank, workers;  // shard, shard count, rank in it, its workgroups
+};
+__device__ __forceinline__ Shard shard_of() {
+  Shard h;
+  h.S = (int)gridDim.x < kTickShards ? (int)gridDim.x : kTickShards;
+  h.s = (int)blockIdx.x % h.S;
+  h.rank = (int)blockIdx.x / h.S;
+  h.workers = ((int)gridDim.x - h.s + h.S - 1) / h.S;
+  return h;
+}
+__device__ __forceinline__ int shard_len(const Shard& h, int n_act) {
+  return n_act > h.s ? (n_act - h.s + h.S - 1) / h.S : 0;
+}
+__device__ __forceinline__ int first_item(const Shard& h, int n_act) {
+  return h.rank < shard_len(h, n_act) ? h.s + h.S * h.rank : -1;
+}
+// Thread 0 draws the ticket for the entry after the current one before
+// visiting it, so the atomic's round trip overlaps the visit; ticket_item
+// then turns it into that entry (or -1).  Draws happen only where the shard
+// hands out tickets this round.
+__device__ __forceinline__ uint32_t draw_ticket(uint32_t* tick, const Shard& h, int n_act) {
+  uint32_t t = 0;
+  if (threadIdx.x == 0 && shard_len(h, n_act) > h.workers)
+    t = __hip_atomic_fetch_add(&tick[h.s * kTickStride], 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+  return t;
+}
+__device__ __forceinline__ int ticket_item(const Shard& h, uint32_t base, int n_act, uint32_t t) {
+  const int n = shard_len(h, n_act);
+  if (n <= h.workers) return -1;  // every entry of the shard was a first one
   __shared__ uint32_t s_ticket;
-  if (threadIdx.x == 0)
-    s_ticket = __hip_atomic_fetch_add(&p.bar[3], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) s_ticket = t;
   __syncthreads();
   const uint32_t d = s_ticket - base;
-  __syncthreads();  // every thread has read the ticket before the next draw
-  return d < (uint32_t)n_act ? (int)d : -1;
+  __syncthreads();  // every thread has read the ticket before the next one lands
+  return d < (uint32_t)(n - h.workers) ? h.s + h.S * (h.workers + (int)d) : -1;
+}
+__device__ __forceinline__ uint32_t round_tickets(const Shard& h, int n_act) {
+  const int n = shard_len(h, n_act);
+  return n > h.workers ? (uint32_t)n : 0u;
 }
 
 // Device-wide barrier; false if aborted.  Release before arriving and

@@ -63,7 +63,7 @@ struct T3Args {
   const int32_t* oz;
   int32_t* flags;    // [2][n_tiles] by round parity
   int32_t* list;     // [2][n_tiles] tiles active in a round
-  int32_t* counter;  // [max_rounds + 2]
+  int32_t* counter;  // [counter_words(max_rounds)]: list lengths, then tickets
   int32_t* err;
   unsigned long long* stats;  // [kStatSlots][16] shards of: [0] visits, [1] edges examined
   // the caller's abort word (device view of pinned host memory, nullable)
@@ -377,16 +377,19 @@ __global__ void __launch_bounds__(kT3Threads) k_tile3_tau(T3Args a, int round) {
 // rounds to convergence, -1 cap reached, -2 barrier timed out, -3 aborted.
 template <int G>
 __global__ void __launch_bounds__(kT3Threads) k_tile3_persist(T3Args a, PersistArgs p) {
-  uint32_t base = 0;  // work tickets issued before this round
+  const Shard sh = shard_of();
+  uint32_t base = 0;  // tickets of this workgroup's shard issued before this round
   for (int round = 0; round < p.max_rounds; ++round) {
     const int n_act =
         __hip_atomic_load(&a.counter[round], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int32_t* lst = a.list + (int64_t)(round & 1) * a.n_tiles;
-    for (int i = next_item(p, base, n_act); i >= 0; i = next_item(p, base, n_act)) {
+    for (int i = first_item(sh, n_act); i >= 0;) {
+      const uint32_t t = draw_ticket(p.tick, sh, n_act);  // the next entry's, in flight meanwhile
       visit3<G>(a, round, lst[i]);
       __syncthreads();  // LDS is reused by the next tile
+      i = ticket_item(sh, base, n_act, t);
     }
-    base += (uint32_t)n_act + gridDim.x;
+    base += round_tickets(sh, n_act);
     if (a.abort_host && blockIdx.x == 0 && threadIdx.x == 0 &&
         __hip_atomic_load(a.abort_host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
       __hip_atomic_store(a.abort_seen, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -451,7 +454,7 @@ int plan_t3(const Tile3Job* jobs, int n_jobs, const Tile3Prob* probs, int n_prob
   P->off_list = off;
   off += align256_t3((size_t)2 * P->n_tiles * sizeof(int32_t));
   P->off_counter = off;
-  off += align256_t3((size_t)(max_rounds + 2) * sizeof(int32_t));
+  off += align256_t3(counter_words(max_rounds) * sizeof(int32_t));  // counts, tickets
   P->off_err = off;
   off += 256;
   P->off_stats = off;
@@ -494,10 +497,11 @@ int run_persistent(const T3Plan& P, const T3Args& a, int push_group, int max_rou
   const int grid = (int)(P.n_tiles < resident ? P.n_tiles : resident);
   PersistArgs pa{};
   pa.max_rounds = max_rounds;
-  pa.bar = (uint32_t*)(a.err + 48);  // [0] arrivals, [1] generation, [2] abort, [3] tickets
+  pa.bar = (uint32_t*)(a.err + 48);  // [0] arrivals, [1] generation, [2] abort
   pa.result = a.err + 52;
+  pa.tick = (uint32_t*)a.counter + tick_offset(max_rounds);
   CHERT_LAUNCH("k_tile3_clear", k_tile3_clear, dim3(256), dim3(256), 0, s, a.flags,
-               (int64_t)2 * P.n_tiles, a.counter, max_rounds + 2, a.err, a.stats);
+               (int64_t)2 * P.n_tiles, a.counter, (int)counter_words(max_rounds), a.err, a.stats);
   CHERT_LAUNCH("k_tile3_seed", k_tile3_seed, dim3((a.n_prob + 63) / 64), dim3(64), 0, s, a);
   CHERT_LAUNCH("k_tile3_persist", kern, dim3((unsigned)grid), dim3((unsigned)threads), P.lds, s,
                a, pa);
@@ -611,7 +615,7 @@ int relax_tiles_3d(const Tile3Job* jobs, int n_jobs, const Tile3Prob* probs, int
   const int64_t resident = (int64_t)per_cu * cus;
   const int grid = (int)(P.n_tiles <= 4 * resident ? P.n_tiles : 4 * resident);
   CHERT_LAUNCH("k_tile3_clear", k_tile3_clear, dim3(256), dim3(256), 0, s, a.flags,
-               (int64_t)2 * P.n_tiles, a.counter, max_rounds + 2, a.err, a.stats);
+               (int64_t)2 * P.n_tiles, a.counter, (int)counter_words(max_rounds), a.err, a.stats);
   CHERT_LAUNCH("k_tile3_seed", k_tile3_seed, dim3((n_prob + 63) / 64), dim3(64), 0, s, a);
   const int batch = 8;
   int32_t counts[batch];

@@ -150,6 +150,7 @@ struct RelaxArgs {
   int32_t* flags;    // [2][n_tiles]
   int32_t* list;     // [2][n_tiles] tiles active in a round (by round parity)
   int32_t* counter;  // [max_rounds + 2] tiles active in each round
+  uint32_t* tick;    // [2][kTickWords] work tickets of the per-round list walk, by round parity
   int32_t* err;      // out-of-range class ids seen
   unsigned long long* stats;  // [kStatSlots][16] shards of: [phase][visits, edges],
                               // levels sum [6 + phase], levels max [9 + phase]
@@ -371,7 +372,7 @@ __global__ void k_clear_flags(int32_t* flags, int64_t n_flags, int32_t* counter,
   for (int64_t t = tid; t < n_counter; t += (int64_t)gridDim.x * blockDim.x) counter[t] = 0;
   for (int64_t t = tid; t < n_key; t += (int64_t)gridDim.x * blockDim.x) key[t] = kInfBits;
   for (int64_t t = tid; t < n_pmin; t += (int64_t)gridDim.x * blockDim.x) pmin[t] = kInfBits;
-  if (tid < 4) bar[tid] = 0u;  // barrier arrivals, generation, abort, work tickets
+  if (tid < 3) bar[tid] = 0u;  // barrier arrivals, generation, abort
 }
 
 // activate the source tile of every problem (tree phase: only problems
@@ -1361,9 +1362,26 @@ __device__ __forceinline__ void round_tiles(const RelaxArgs& a, int round) {
   }
   const int n_act = a.counter[round];
   const int32_t* lst = a.list + (int64_t)(round & 1) * a.n_tiles;
-  for (int i = blockIdx.x; i < n_act; i += gridDim.x) {
-    visit<G, PH>(a, round, lst[i]);
-    __syncthreads();  // LDS is reused by the next tile
+  if constexpr (PH == 0) {
+    // tau visits differ in length by tens of levels: after its first entry
+    // a workgroup takes the next by ticket as it frees up.  The next
+    // round's ticket lines (last used a round ago) start from zero.
+    if (blockIdx.x == 0 && threadIdx.x < kTickWords)
+      a.tick[((round + 1) & 1) * kTickWords + threadIdx.x] = 0u;
+    uint32_t* tick = a.tick + (round & 1) * kTickWords;
+    const Shard sh = shard_of();
+    for (int i = first_item(sh, n_act); i >= 0;) {
+      const uint32_t t = draw_ticket(tick, sh, n_act);  // the next entry's, in flight meanwhile
+      visit<G, PH>(a, round, lst[i]);
+      __syncthreads();  // LDS is reused by the next tile
+      i = ticket_item(sh, 0u, n_act, t);
+    }
+  } else {
+    // tree visits: dealt round-robin (tickets measured slower here)
+    for (int i = blockIdx.x; i < n_act; i += gridDim.x) {
+      visit<G, PH>(a, round, lst[i]);
+      __syncthreads();  // LDS is reused by the next tile
+    }
   }
 }
 // LEAN: at most 64 VGPRs (8 waves per SIMD; not for G = 4, which would
@@ -1390,7 +1408,8 @@ k_relax_tree(RelaxArgs a, int round) {
 
 template <int G, int PH>
 __global__ void __launch_bounds__(kRelaxThreads) k_relax_persist(RelaxArgs a, PersistArgs p) {
-  uint32_t base = 0;  // work tickets issued before this round
+  const Shard sh = shard_of();
+  uint32_t base = 0;  // tickets of this workgroup's shard issued before this round
   for (int round = 0; round < p.max_rounds; ++round) {
     if (blockIdx.x == 0) reset_pmin(a, round);
     const int n_act =
@@ -1398,13 +1417,20 @@ __global__ void __launch_bounds__(kRelaxThreads) k_relax_persist(RelaxArgs a, Pe
     const int32_t* lst = a.list + (int64_t)(round & 1) * a.n_tiles;
     // visits differ in length by tens of levels: tiles are handed out as
     // workgroups free up rather than dealt round-robin
-    for (int i = next_item(p, base, n_act); i >= 0; i = next_item(p, base, n_act)) {
+    for (int i = first_item(sh, n_act); i >= 0;) {
       const int T = lst[i];
-      if constexpr (PH == 0) relax_tau<G>(a, round, T);
-      else relax_tree(a, round, T);
+      uint32_t t;
+      if constexpr (PH == 0) {
+        t = draw_ticket(p.tick, sh, n_act);  // the next entry's, in flight during the visit
+        relax_tau<G>(a, round, T);
+      } else {
+        relax_tree(a, round, T);  // short visits, tight on registers: drawn after
+        t = draw_ticket(p.tick, sh, n_act);
+      }
       __syncthreads();  // LDS is reused by the next tile
+      i = ticket_item(sh, base, n_act, t);
     }
-    base += (uint32_t)n_act + gridDim.x;
+    base += round_tickets(sh, n_act);
     // the caller's abort word, polled once per round by workgroup 0 and
     // published by the barrier below, so every workgroup leaves together
     if (a.abort_host && blockIdx.x == 0 && threadIdx.x == 0 && host_abort(a))
@@ -1609,7 +1635,7 @@ static int make_plan(const chert_trace_job* jobs, int n_jobs, const chert_trace_
   P->off_list = off;
   off += align256((size_t)2 * P->n_tiles * sizeof(int32_t));
   P->off_counter = off;
-  off += align256((size_t)(P->max_rounds + 2) * sizeof(int32_t));
+  off += align256(counter_words(P->max_rounds) * sizeof(int32_t));  // counts, tickets
   P->off_key = off;
   off += align256((size_t)2 * P->n_tiles * sizeof(uint64_t));
   P->off_pmin = off;
@@ -1879,6 +1905,8 @@ static int prepare(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
   Q->pa.max_rounds = P.max_rounds;
   Q->pa.bar = (uint32_t*)(ws + P.off_err + 192);
   Q->pa.result = (int32_t*)(ws + P.off_err + 208);
+  Q->pa.tick = (uint32_t*)(ws + P.off_counter) + tick_offset(P.max_rounds);
+  Q->a.tick = Q->pa.tick;
   Q->ws = ws;
   Q->djobs = djobs;
   Q->dprobs = dprobs;
@@ -1980,7 +2008,7 @@ static int enqueue(const Prepared& Q, const chert_trace_job* jobs, int n_jobs,
   const int64_t n_flags = 2 * P.n_tiles;
   auto init_flags = [&](int tree_phase) {
     CHERT_LAUNCH("k_clear_flags", k_clear_flags, dim3(256), dim3(256), 0, s, a.flags, n_flags,
-                 a.counter, P.max_rounds + 2, pa.bar, a.key, 2 * P.n_tiles, a.pmin,
+                 a.counter, (int)counter_words(P.max_rounds), pa.bar, a.key, 2 * P.n_tiles, a.pmin,
                  3 * P.n_prob);
     CHERT_LAUNCH("k_seed_flags", k_seed_flags, dim3((P.n_prob + 63) / 64), dim3(64), 0, s,
                  a.flags, a.list, a.counter, Q.dprobs, Q.djobs, P.n_prob, P.tx, P.tz,
