@@ -64,6 +64,7 @@ struct T3Args {
   int32_t* flags;    // [2][n_tiles] by round parity
   int32_t* list;     // [2][n_tiles] tiles active in a round
   int32_t* counter;  // [counter_words(max_rounds)]: list lengths, then tickets
+  uint32_t* tick;    // [2][kTickWords] tickets of the per-round list walk, by round parity
   int32_t* err;
   unsigned long long* stats;  // [kStatSlots][16] shards of: [0] visits, [1] edges examined
   // the caller's abort word (device view of pinned host memory, nullable)
@@ -364,9 +365,18 @@ __global__ void __launch_bounds__(kT3Threads) k_tile3_tau(T3Args a, int round) {
   }
   const int n_act = a.counter[round];
   const int32_t* lst = a.list + (int64_t)(round & 1) * a.n_tiles;
-  for (int i = blockIdx.x; i < n_act; i += gridDim.x) {
+  // tiles by ticket as workgroups free up; the next round's ticket lines
+  // (last used a round ago) start from zero
+  if (blockIdx.x == 0)
+    for (int q = threadIdx.x; q < kTickWords; q += blockDim.x)
+      a.tick[((round + 1) & 1) * kTickWords + q] = 0u;
+  uint32_t* tick = a.tick + (round & 1) * kTickWords;
+  const Shard sh = shard_of();
+  for (int i = first_item(sh, n_act); i >= 0;) {
+    const uint32_t t = draw_ticket(tick, sh, n_act);  // the next entry's, in flight meanwhile
     visit3<G>(a, round, lst[i]);
     __syncthreads();  // LDS is reused by the next tile
+    i = ticket_item(sh, 0u, n_act, t);
   }
 }
 
@@ -588,6 +598,7 @@ int relax_tiles_3d(const Tile3Job* jobs, int n_jobs, const Tile3Prob* probs, int
   a.counter = (int32_t*)(w + P.off_counter);
   a.err = (int32_t*)(w + P.off_err);
   a.stats = (unsigned long long*)(w + P.off_stats);
+  a.tick = (uint32_t*)a.counter + tick_offset(max_rounds);
   a.abort_seen = a.err + 56;
   a.abort_host = nullptr;
   if (persistent && abort_flag) {

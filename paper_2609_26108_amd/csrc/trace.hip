@@ -1366,8 +1366,9 @@ __device__ __forceinline__ void round_tiles(const RelaxArgs& a, int round) {
     // tau visits differ in length by tens of levels: after its first entry
     // a workgroup takes the next by ticket as it frees up.  The next
     // round's ticket lines (last used a round ago) start from zero.
-    if (blockIdx.x == 0 && threadIdx.x < kTickWords)
-      a.tick[((round + 1) & 1) * kTickWords + threadIdx.x] = 0u;
+    if (blockIdx.x == 0)
+      for (int q = threadIdx.x; q < kTickWords; q += blockDim.x)
+        a.tick[((round + 1) & 1) * kTickWords + q] = 0u;
     uint32_t* tick = a.tick + (round & 1) * kTickWords;
     const Shard sh = shard_of();
     for (int i = first_item(sh, n_act); i >= 0;) {

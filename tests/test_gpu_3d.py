@@ -208,6 +208,30 @@ def test_trace_3d_invalid_class_id_reported(G, small3d, launch):
     assert e.value.code == 1
 
 
+@pytest.mark.parametrize("launch", [0, 1])
+def test_trace_3d_list_walk_small_tiles_bitwise(G, launch):
+    """4 x 4 x 4 tiles (one wavefront each) over a 48 x 48 x 32 grid, two
+    sources and both fields: 4,608 tiles, more than four times the resident
+    workgroups, so the per-round launches walk each round's list by ticket
+    (and the persistent one hands its list out likewise); every traveltime
+    equals the oracle's Dijkstra bitwise."""
+    Cm = C()
+    m = W.config5(nx=48, ny=48, nz=32, n_interfaces=3, radius=3,
+                  sources=((7, 9, 0), (40, 30, 31)))
+    cls = model_classes(m)
+    f, s = O.build_cache_3d(cls, N=400, mode_mask=0b001, n_sweep=360)
+    K = cls.shape[0]
+    desc = Cm.cache_desc(dim=3, n_dirs=400, modes=(0,), n_sweep=360)
+    cache = G.import_cache(f, s, desc, K)
+    tr, ti, st = trace3(G, m, cache, desc, K, 0, launch=launch, tile=(4, 4), group=2)
+    print(st, flush=True)
+    for si, src in enumerate(m.sources):
+        o = O.trace_3d(m.nx, m.ny, m.nz, m.h, m.h, m.h, m.class_id, m.radius, f[0, 0], f[1, 0],
+                       s[0], src, N=400)
+        assert np.array_equal(tr[si], o["tauR"]), (si, int(np.sum(tr[si] != o["tauR"])))
+        assert np.array_equal(ti[si], o["tauI"]), si
+
+
 def _abort_word(value):
     w = torch.zeros(1, dtype=torch.int32).pin_memory()
     w[0] = value

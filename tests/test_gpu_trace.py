@@ -424,12 +424,15 @@ def test_lean_builds_per_node_many_sources_bitwise(G):
         assert_fields_equal(g, o, si)
 
 
-def test_list_mode_bitwise(G):
+@pytest.mark.parametrize("tile,n_src", [((32, 32), 64), ((8, 8), 32)])
+def test_list_mode_bitwise(G, tile, n_src):
     """A batch with more tiles than four times the resident workgroups (64
-    sources x 2 fields x 20 tiles of 32 x 32 = 2560): the per-round launches
-    walk each round's list of active tiles instead of one workgroup per
-    tile.  Eager and as a replayed graph, every field, t* and predecessor
-    equals the oracle's bitwise."""
+    sources x 2 fields x 20 tiles of 32 x 32 = 2560; or 32 x 2 x 320 tiles
+    of 8 x 8 = 20,480, one wavefront each, more than four times 20 resident
+    per compute unit): the per-round launches walk each round's list of
+    active tiles (tau by ticket, from counters a workgroup of any size
+    clears) instead of one workgroup per tile.  Eager and as a replayed
+    graph, every field, t* and predecessor equals the oracle's bitwise."""
     Cm = C()
     m = W.small_layered(nx=160, nz=128, radius=3, seed=31)
     cls, f, s = oracle_cache(m, (0,), n_sweep=720)
@@ -437,7 +440,7 @@ def test_list_mode_bitwise(G):
     desc = Cm.cache_desc(n_dirs=360, modes=(0,), n_sweep=720)
     cache = G.import_cache(f, s, desc, K)
     rng = np.random.default_rng(77)
-    srcs = sorted(rng.choice(m.n_nodes, 64, replace=False).tolist())
+    srcs = sorted(rng.choice(m.n_nodes, n_src, replace=False).tolist())
     cid = torch.from_numpy(m.class_id.reshape(-1).astype(np.int32)).to(G.DEV)
     grid = Cm.make_grid(m.nx, m.nz, m.hx, m.hz, m.radius, cid)
     n, S = m.n_nodes, len(srcs)
@@ -448,14 +451,14 @@ def test_list_mode_bitwise(G):
     b = Cm.Batch()
     b.add(desc, cache, K, grid, 0, srcs, **out)
     st = Cm.TraceStats()
-    opts = Cm.trace_opts(Cm.OUT_ALL, 32, 32, stats=st)
+    opts = Cm.trace_opts(Cm.OUT_ALL, tile[0], tile[1], stats=st)
     ws = torch.empty(Cm.chert_trace_batch_workspace_bytes(b, opts), dtype=torch.uint8,
                      device=G.DEV)
     Cm.chert_trace_batch(b, opts, ws)
     torch.cuda.synchronize()
     print(st.as_dict(), flush=True)
     eager = {k: v.clone() for k, v in out.items()}
-    gopts = Cm.trace_opts(Cm.OUT_ALL, 32, 32, max_rounds=max(st.rounds) + 8)
+    gopts = Cm.trace_opts(Cm.OUT_ALL, tile[0], tile[1], max_rounds=max(st.rounds) + 8)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         graph = Cm.TraceGraph(b, gopts, ws, stream=stream)
