@@ -211,7 +211,7 @@ def test_trace_3d_invalid_class_id_reported(G, small3d, launch):
 @pytest.mark.parametrize("launch", [0, 1])
 def test_trace_3d_list_walk_small_tiles_bitwise(G, launch):
     """4 x 4 x 4 tiles (one wavefront each) over a 48 x 48 x 32 grid, two
-    sources and both fields: 4,608 tiles, more than four times the resident
+    sources and both fields: 4,608 tiles, more than twice the resident
     workgroups, so the per-round launches walk each round's list by ticket
     (and the persistent one hands its list out likewise); every traveltime
     equals the oracle's Dijkstra bitwise."""
