@@ -439,10 +439,12 @@ int chert_trace_batch(const chert_trace_job *jobs, int32_t n_jobs,
  * persistent launch, then, if tiles win, their ordering width 16, 64 or 256
  * on the fastest shape.  Each is timed (HIP events,
  * second of two runs) on a probe batch made of the first source of every
- * job; the fastest is written into o->tile_x, tile_z, push_group, launch and
- * bucket_width (other fields are kept) and its probe time into *best_ms
- * (nullable).  The probe writes the first source's
- * rows of the jobs' outputs.  The workspace must hold
+ * job; when some job has more than one source, the three fastest are timed
+ * the same way on the whole batch.  The fastest is written into o->tile_x,
+ * tile_z, push_group, launch and bucket_width (other fields are kept) and
+ * its time (on the whole batch when it was timed there, else on the probe)
+ * into *best_ms (nullable).  The runs write the jobs' outputs (the probe
+ * the first source's rows).  The workspace must hold
  * chert_trace_autotune_workspace_bytes (which also covers the full batch
  * under any candidate).  Synchronous. */
 size_t chert_trace_autotune_workspace_bytes(const chert_trace_job *jobs, int32_t n_jobs,

@@ -2192,6 +2192,7 @@ const int kTuneTiles3D[][2] = {{8, 8}, {8, 16}, {16, 4}, {4, 16}};
 const int kTuneGroups[] = {1, 2, 4};        // 3D tiles
 const int kTuneGroups2D[] = {1, 2, 4, 8};   // 2D tiles
 const int kTuneLaunch[] = {CHERT_LAUNCH_PER_ROUND, CHERT_LAUNCH_PERSISTENT};
+constexpr int kTuneFinal = 3;  // probe winners timed again on the whole batch
 }  // namespace
 
 const double kTuneBuckets[] = {0.0, 4.0, 16.0, 32.0, 64.0, 128.0, 256.0};
@@ -2284,21 +2285,28 @@ extern "C" int chert_trace_autotune(const chert_trace_job* jobs, int32_t n_jobs,
   double best = -1.0;
   chert_trace_opts pick = *o;
   int tried = 0;
-  auto consider = [&](chert_trace_opts c) {
+  std::vector<std::pair<float, chert_trace_opts>> timed;  // every candidate that ran
+  // time c on a batch (HIP events, the second of two runs); false if it
+  // does not fit the workspace or fails
+  auto time_on = [&](const chert_trace_job* b, chert_trace_opts c, float* ms) {
     c.stats_host = nullptr;
-    const size_t need = chert_trace_batch_workspace_bytes(probe.data(), n_jobs, &c);
-    if (need == 0 || need > workspace_bytes) return;  // shape not valid here
+    const size_t need = chert_trace_batch_workspace_bytes(b, n_jobs, &c);
+    if (need == 0 || need > workspace_bytes) return false;  // shape not valid here
     int rc = CHERT_OK;
-    float ms = 0.f;
-    for (int rep = 0; rep < 2 && rc == CHERT_OK; ++rep) {  // second run is timed
+    for (int rep = 0; rep < 2 && rc == CHERT_OK; ++rep) {
       (void)hipEventRecord(e0, s);
-      rc = trace_batch(probe.data(), n_jobs, &c, workspace_dev, workspace_bytes, s);
+      rc = trace_batch(b, n_jobs, &c, workspace_dev, workspace_bytes, s);
       (void)hipEventRecord(e1, s);
       if (hipEventSynchronize(e1) != hipSuccess) rc = CHERT_ERR_HIP;
-      if (rc == CHERT_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rc == CHERT_OK) (void)hipEventElapsedTime(ms, e0, e1);
     }
-    if (rc != CHERT_OK) return;
+    return rc == CHERT_OK;
+  };
+  auto consider = [&](chert_trace_opts c) {
+    float ms = 0.f;
+    if (!time_on(probe.data(), c, &ms)) return;
     ++tried;
+    timed.emplace_back(ms, c);
     if (best < 0.0 || ms < best) {
       best = ms;
       pick = c;
@@ -2313,6 +2321,25 @@ extern "C" int chert_trace_autotune(const chert_trace_job* jobs, int32_t n_jobs,
       c.bucket_width = bw;
       consider(c);
     }
+  // the probe's few fastest, timed again on the whole batch: a probe of one
+  // source per job can rank shapes differently from many sources
+  bool partial = false;
+  for (int j = 0; j < n_jobs; ++j) partial |= jobs[j].n_src > 1;
+  if (partial && tried > 1) {
+    std::stable_sort(timed.begin(), timed.end(),
+                     [](const std::pair<float, chert_trace_opts>& x,
+                        const std::pair<float, chert_trace_opts>& y) { return x.first < y.first; });
+    double whole = -1.0;
+    for (size_t q = 0; q < timed.size() && q < (size_t)kTuneFinal; ++q) {
+      float ms = 0.f;
+      if (!time_on(jobs, timed[q].second, &ms)) continue;
+      if (whole < 0.0 || ms < whole) {
+        whole = ms;
+        pick = timed[q].second;
+      }
+    }
+    if (whole >= 0.0) best = whole;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (tried == 0) return fail(CHERT_ERR_INVALID_ARG, "no candidate fits the workspace");
