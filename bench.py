@@ -52,13 +52,14 @@ FP64_VALU_PEAK_TOPS = 39.3  # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz, one o
 # Valid only for the kernel source it was measured on.
 MEASURED_TRAFFIC = {
     "source": "paper_2609_26108_amd/csrc/trace.hip",
-    "source_sha256_16": "15b01e642bd947be",
+    "source_sha256_16": "623475a67b7c636d",
     "fetch_scale": 2.0, "write_scale": 1.0,
     # workload -> kernel -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
     # (profiles/k_relax_tau__shots_4_grids_per_node.md: one step, 16 x 64
-    # tiles, push group 4, 112 dispatches of each relaxation kernel)
-    "kib_per_dispatch": {"shots": {"k_relax_tau": (861626.83, 11315.49),
-                                   "k_relax_tree": (256485.15, 40219.90)}},
+    # tiles, push group 4; 112 tau and 176 tree dispatches, the last 64 of
+    # the tree's past convergence)
+    "kib_per_dispatch": {"shots": {"k_relax_tau": (860848.77, 10967.56),
+                                   "k_relax_tree": (165424.19, 54643.38)}},
 }
 
 
