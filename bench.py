@@ -52,14 +52,13 @@ FP64_VALU_PEAK_TOPS = 39.3  # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz, one o
 # Valid only for the kernel source it was measured on.
 MEASURED_TRAFFIC = {
     "source": "paper_2609_26108_amd/csrc/trace.hip",
-    "source_sha256_16": "623475a67b7c636d",
+    "source_sha256_16": "7c4a616df9a01d8a",
     "fetch_scale": 2.0, "write_scale": 1.0,
     # workload -> kernel -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
     # (profiles/k_relax_tau__shots_4_grids_per_node.md: one step, 16 x 64
-    # tiles, push group 4; 112 tau and 176 tree dispatches, the last 64 of
-    # the tree's past convergence)
-    "kib_per_dispatch": {"shots": {"k_relax_tau": (860848.77, 10967.56),
-                                   "k_relax_tree": (165424.19, 54643.38)}},
+    # tiles, push group 4, 112 dispatches of each relaxation kernel)
+    "kib_per_dispatch": {"shots": {"k_relax_tau": (861622.49, 10930.35),
+                                   "k_relax_tree": (261086.43, 54668.11)}},
 }
 
 

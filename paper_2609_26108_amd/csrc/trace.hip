@@ -1932,13 +1932,16 @@ static int prepare(const chert_trace_job* jobs, int n_jobs, const chert_trace_op
       rc = persist_grid((const void*)round_kernel(ph, G, Q->lean), tile_threads(P.tx, P.tz), Q->lds[ph],
                         P.n_tiles, &Q->rgrid[ph]);
     if (rc) return rc;
-    // per-round launches: one workgroup per tile while that is at most
-    // `over` times the resident workgroups (tile affinity), else `over`
-    // times the resident workgroups walking the active list: twice for the
-    // tau phase, whose tiles go out by ticket, eight times for the tree
-    // phase, dealt round-robin and balanced by the dispatcher
-    const int64_t over = ph == 0 ? 2 : 8;
-    Q->rgrid[ph] = (int)std::min<int64_t>(P.n_tiles, over * (int64_t)Q->rgrid[ph]);
+    // per-round launches: one workgroup per tile (tile affinity) while that
+    // is at most 4x the resident workgroups (tree phase: 8x), else a list
+    // walk by twice the resident workgroups for the tau phase, whose tiles
+    // go out by ticket, and eight times for the tree phase, dealt
+    // round-robin and balanced by the dispatcher
+    const int64_t res = Q->rgrid[ph];
+    if (ph == 0)
+      Q->rgrid[ph] = (int)(P.n_tiles <= 4 * res ? P.n_tiles : 2 * res);
+    else
+      Q->rgrid[ph] = (int)std::min<int64_t>(P.n_tiles, 8 * res);
   }
   return CHERT_OK;
 }
