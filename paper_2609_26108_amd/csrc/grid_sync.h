@@ -2,7 +2,9 @@
 // tiles): an occupancy-sized grid walks each round's active tiles and
 // separates rounds with this barrier.  Its wait is bounded: a workgroup that
 // waits longer than kBarrierWaitTicks (or sees another's abort) raises the
-// abort word and leaves, so every wave exits.
+// abort word and leaves, so every wave exits.  Also the ticket hand-out of
+// a round's active tiles used by the persistent and the per-round list
+// walks.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,9 +14,9 @@ namespace chert {
 
 constexpr uint64_t kBarrierWaitTicks = 200000000ull;  // 2 s of the 100 MHz real-time clock
 
-// Work-ticket counters of the persistent launches: one 128-byte line per
-// shard, so that draws spread over several addresses (atomics on one
-// address serialise across the chip).
+// Work-ticket counters of the list walks: one 128-byte line per shard, so
+// that draws spread over several addresses (atomics on one address
+// serialise across the chip).
 constexpr int kTickShards = 8;
 constexpr int kTickStride = 32;  // 32-bit words between shards
 constexpr int kTickWords = kTickShards * kTickStride;
@@ -36,7 +38,7 @@ struct PersistArgs {
   uint32_t* tick;   // [kTickWords] zeroed before the launch, never reset during it
 };
 
-// Dynamic hand-out of a round's n_act list entries to the persistent grid.
+// Dynamic hand-out of a round's n_act list entries to the grid.
 // The entries and workgroups are split into S = min(kTickShards, gridDim.x)
 // shards by index mod S.  Within its shard a workgroup of rank r takes entry
 // r first (no atomic, so a round does not start with every workgroup
@@ -44,9 +46,10 @@ struct PersistArgs {
 // workgroups, each draws one ticket per entry it visits from the shard's
 // counter for the remaining ones, and stops at its first ticket past them.
 // Such a shard issues exactly as many tickets per round as it has entries,
-// a shorter one none; the counters are never reset, so every workgroup
-// advances its shard's `base` alike (round_tickets), differences taken
-// modulo 2^32.
+// a shorter one none.  The persistent launch never resets its counters, so
+// every workgroup advances its shard's `base` alike (round_tickets),
+// differences taken modulo 2^32; the per-round launches use a zeroed set of
+// counters per round (base 0).
 struct Shard {
   int s, S, rank, workers;  // shard, shard count, rank in it, its workgroups
 };
